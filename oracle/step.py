@@ -1,0 +1,86 @@
+"""One ACSE propagation step and the energy, on the stored singlet blocks (oracle).
+
+Inputs are the spatial quantities the GPU library takes: h [r,r], chemists'
+V [r,r,r,r], N, the alpha 1-RDM gamma [r,r] and the 2-RDM blocks d2aa, d2ab
+[r,r,r,r] (Eq. (6) normalisation).  Everything is lifted to spin orbitals
+(``rdm.blocks_to_spin_orbital``) and computed there; the returned blocks are
+the alpha-alpha and (p_a q_b | r_a s_b) parts.
+
+Readings:
+* Active mask (the "all active" option of the method section): ``active`` is
+  a per-spatial-orbital flag; a residual element is zeroed iff all four of its
+  spatial indices are active, in every spin block.  The residual norm is
+  taken before masking.
+* Update scale: U = F(R_m) = 1/2 <[O, A]> = d 2D / d eps along exp(eps A) psi,
+  with A = sum R_m a+a+aa;  2D_{n+1} = 2D_n + eps U  (Eq. (9)).
+* Trace restoration: the paper describes none; Tr U = 0 per block in exact
+  arithmetic, so each block is rescaled to its input trace (removes rounding
+  drift only).
+* 1-RDM after the step: the contraction 1D = 2/(N-1) sum_q 2D[p,q,r,q].
+"""
+import numpy as np
+import torch
+
+from . import rdm
+from .residual import residual_map
+
+
+def active_mask(active, r):
+    """Spin-orbital mask, True where the element is kept."""
+    if active is None:
+        return None
+    act = np.asarray(active, dtype=bool)
+    so = np.concatenate([act, act])
+    all4 = so[:, None, None, None] & so[None, :, None, None] & so[None, None, :, None] & so[None, None, None, :]
+    return ~all4
+
+
+def norm2_spin_orbital(t4):
+    return float(np.sum(np.asarray(t4) ** 2))
+
+
+def energy(h, V, N, d2aa, d2ab):
+    """E = Tr(K 2D) over spin orbitals (Eq. (2) with Eq. (6))."""
+    r = h.shape[0]
+    K = rdm.reduced_hamiltonian(h, V, N)
+    _, d2 = rdm.blocks_to_spin_orbital(np.eye(r), d2aa, d2ab)
+    return float(np.sum(K * d2))
+
+
+def residual(h, V, N, gamma, d2aa, d2ab):
+    """R = F(K) (Eq. (4)); returns (R_aa, R_ab, ||R||^2 over spin orbitals)."""
+    K = rdm.reduced_hamiltonian(h, V, N)
+    d1, d2 = rdm.blocks_to_spin_orbital(gamma, d2aa, d2ab)
+    R = residual_map(K, d1, d2, hermitian=True).numpy()
+    raa, rab = rdm.spin_orbital_to_blocks(R)
+    return raa, rab, norm2_spin_orbital(R)
+
+
+def step(h, V, N, gamma, d2aa, d2ab, eps, active=None, keep_spin_orbital=False):
+    """One Euler step (Eq. (9)).  Returns a dict of blocks and scalars."""
+    r = h.shape[0]
+    K = rdm.reduced_hamiltonian(h, V, N)
+    d1, d2 = rdm.blocks_to_spin_orbital(gamma, d2aa, d2ab)
+    R = residual_map(K, d1, d2, hermitian=True).numpy()
+    n2 = norm2_spin_orbital(R)
+    mask = active_mask(active, r)
+    Rm = R if mask is None else R * mask
+    U = residual_map(Rm, d1, d2, hermitian=False).numpy()
+    raa, rab = rdm.spin_orbital_to_blocks(R)
+    uaa, uab = rdm.spin_orbital_to_blocks(U)
+    d2aa_1 = d2aa + eps * uaa
+    d2ab_1 = d2ab + eps * uab
+    t0aa, t0ab = rdm.block_traces(d2aa, d2ab)
+    t1aa, t1ab = rdm.block_traces(d2aa_1, d2ab_1)
+    d2aa_1 = d2aa_1 * (t0aa / t1aa)
+    d2ab_1 = d2ab_1 * (t0ab / t1ab)
+    _, d2_1 = rdm.blocks_to_spin_orbital(gamma, d2aa_1, d2ab_1)
+    gamma_1 = rdm.contract_to_1rdm(d2_1, N)[:r, :r]
+    e1 = float(np.sum(K * d2_1))
+    out = dict(R_aa=raa, R_ab=rab, norm2=n2, U_aa=uaa, U_ab=uab,
+               d2aa=d2aa_1, d2ab=d2ab_1, gamma=gamma_1, energy=e1,
+               energy0=float(np.sum(K * d2)),
+               trace_scale=(t0aa / t1aa, t0ab / t1ab))
+    if keep_spin_orbital:
+        out.update(R=R, U=U, Rm=Rm, K=K, d1=d1, d2=d2)
+    return out
