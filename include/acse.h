@@ -1,0 +1,150 @@
+/*
+ * acse.h -- C ABI of the MI355X (gfx950) ACSE residual library, libacse.so.
+ *
+ * The library evaluates the hot path of the anti-Hermitian contracted
+ * Schroedinger equation (ACSE, arXiv 2604.02550) for singlet-type states:
+ *
+ *   residual  R^{ij}_{kl} = <psi| [a+_i a+_j a_l a_k, H] |psi>        (Eq. (4))
+ *             with the 3-RDM rebuilt by Valdemoro cumulant reconstruction
+ *             (Eq. (7) with 3Delta = 0; App. C, Eq. (C5)) and never stored,
+ *   update    U = 1/2 <[a+a+aa, A]>, A = sum R_m a+a+aa,  2D <- 2D + eps U  (Eq. (9)),
+ *   energy    E = Tr(K 2D) with the reduced Hamiltonian K of Eq. (2).
+ *
+ * Conventions (all arrays row-major, FP64, caller-owned):
+ *   r          number of spatial orbitals; indices p,q,r,s in [0, r).
+ *   h[r*r]     one-electron integrals 1K (symmetric).
+ *   V[r^4]     two-electron integrals in chemists' notation V[p,q,r,s] = (pq|rs)
+ *              (8-fold symmetric).  The reduced Hamiltonian of Eq. (2) is
+ *              K^{pq}_{rs} = (pr|qs) + (h_pr d_qs + h_qs d_pr)/(N-1) on every
+ *              spin block, so that H = 1/2 sum K a+_p a+_q a_s a_r and E = Tr(K 2D).
+ *   d1[r*r]    alpha 1-RDM  1D[p,r] = <a+_pa a_ra>  (beta is equal).
+ *   d2aa[r^4]  2D(pa qa | ra sa) = 1/2 <a+_pa a+_qa a_sa a_ra>     (Eq. (6))
+ *   d2ab[r^4]  2D(pa qb | ra sb) = 1/2 <a+_pa a+_qb a_sb a_ra>
+ *              (the beta-beta block equals alpha-alpha; App. A traces
+ *              Tr d2aa = Na(Na-1)/2, Tr d2ab = Na Nb/2).
+ *   R_aa, R_ab the residual blocks R(ia ja | ka la), R(ia jb | ka lb), same layout.
+ *   ||R||^2    the squared Frobenius norm over all spin-orbital elements,
+ *              2 ||R_aa||^2 + 4 ||R_ab||^2, taken before the active mask.
+ *
+ * Sign: Eq. (4) is followed (R = +<[O,H]>); Eq. (5) as printed gives -R.  The
+ * update U is even in this sign.
+ *
+ * Memory: h, V, d1, d2aa, d2ab and all outputs are DEVICE pointers on the
+ * context's device, 16-byte aligned, owned by the caller.  Outputs ending in
+ * _host are host pointers.  The library owns only its workspace, allocated in
+ * acse_create for a maximum size r_max and released in acse_destroy; it keeps
+ * no caller pointer after a call returns.
+ *
+ * Streams: every call is ordered on the context's HIP stream.  Calls that
+ * return a host scalar synchronise that stream before returning; the others
+ * return as soon as the work is enqueued.
+ *
+ * Errors: every call returns an acse_status; no C++ exception crosses the ABI.
+ * acse_last_error() gives a human-readable detail for the last failing call
+ * on a context.  A failing call leaves caller outputs unspecified and the
+ * inputs unchanged (acse_step validates before it writes).
+ */
+#ifndef ACSE_H
+#define ACSE_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct acse_ctx_s *acse_ctx;
+
+typedef enum {
+  ACSE_OK = 0,
+  ACSE_ERR_ARG = 1,         /* null pointer, bad enum value, non-finite eps */
+  ACSE_ERR_SHAPE = 2,       /* r < 2, r > r_max, N < 2 or N > 2r */
+  ACSE_ERR_ALIGN = 3,       /* a device pointer is not 16-byte aligned */
+  ACSE_ERR_UNSUPPORTED = 4, /* n_alpha != n_beta (non-singlet blocks), feature not built */
+  ACSE_ERR_NOMEM = 5,       /* workspace allocation failed */
+  ACSE_ERR_HIP = 6,         /* a HIP runtime call failed */
+  ACSE_ERR_NONFINITE = 7    /* ||R||^2 or E came out non-finite */
+} acse_status;
+
+/* Arithmetic of the O(r^6) contractions.  Everything else (folds, the
+ * residual norm, the step, trace restoration, the 1-RDM contraction and the
+ * energy) is FP64 in every mode. */
+typedef enum {
+  ACSE_FP64 = 0,   /* FP64 MFMA (v_mfma_f64_16x16x4) */
+  ACSE_FP32 = 1,   /* FP32 operands, FP32 MFMA accumulation */
+  ACSE_BF16X3 = 2  /* split-BF16 products a_hi b_hi + a_hi b_lo + a_lo b_hi, FP32 accumulation */
+} acse_precision;
+
+typedef struct {
+  int32_t r;          /* spatial orbitals, 2 <= r <= r_max */
+  int32_t n_alpha;    /* alpha electrons */
+  int32_t n_beta;     /* beta electrons; must equal n_alpha (singlet blocks) */
+  const double *h;    /* device [r*r] */
+  const double *V;    /* device [r^4]  */
+  double *d1;         /* device [r*r]  alpha 1-RDM (acse_step overwrites it) */
+  double *d2aa;       /* device [r^4]  (acse_step overwrites it) */
+  double *d2ab;       /* device [r^4]  (acse_step overwrites it) */
+} acse_problem;
+
+typedef struct {
+  int32_t precision;      /* acse_precision */
+  const uint8_t *active;  /* HOST [r]: nonzero = active orbital, or NULL for no mask.
+                             A residual element is zeroed before the update iff all
+                             four of its spatial indices are active (the "all active"
+                             option of the method section); the norm is taken first. */
+  int32_t tile;           /* GEMM tile configuration, -1 = autotuned default */
+} acse_options;
+
+/* Creates a context on HIP device `device`, ordering work on `hip_stream`
+ * (a hipStream_t; NULL = the default stream), with workspace for problems up
+ * to r_max spatial orbitals.  Returns ACSE_ERR_NOMEM if the workspace does
+ * not fit. */
+acse_status acse_create(acse_ctx *out, int device, void *hip_stream, int32_t r_max);
+
+/* Frees the workspace (after synchronising the stream) and the context. */
+acse_status acse_destroy(acse_ctx ctx);
+
+/* Replaces the stream later calls are ordered on. */
+acse_status acse_set_stream(acse_ctx ctx, void *hip_stream);
+
+/* Residual of Eq. (4) (Valdemoro 3-RDM, never stored).  Writes R_aa, R_ab
+ * (device [r^4] each, may not alias inputs) and, if norm2_host is not NULL,
+ * ||R||^2 (synchronises).  The active mask in opts is ignored here. */
+acse_status acse_residual(acse_ctx ctx, const acse_problem *prob, const acse_options *opts,
+                          double *R_aa, double *R_ab, double *norm2_host);
+
+/* Update map of Eq. (9) for a given anti-Hermitian two-body tensor X (blocks
+ * X_aa, X_ab in the layout of R): U = 1/2 <[a+a+aa, sum X a+a+aa]> with the
+ * Valdemoro 3-RDM of the problem's RDMs.  With X = the masked residual this
+ * is the 2-RDM update direction.  Writes U_aa, U_ab (device [r^4]). */
+acse_status acse_update_map(acse_ctx ctx, const acse_problem *prob, const acse_options *opts,
+                            const double *X_aa, const double *X_ab, double *U_aa, double *U_ab);
+
+/* Energy E = Tr(K 2D) = 2<K_s, d2aa> + 2<K_s, d2ab> (Eq. (2), Eq. (6)), FP64.
+ * Synchronises. */
+acse_status acse_energy(acse_ctx ctx, const acse_problem *prob, double *E_host);
+
+/* One Euler step of Eq. (9): R = residual, R_m = mask(R), U = update_map(R_m),
+ * 2D <- 2D + eps U, each 2-RDM block rescaled to its input trace (FP64),
+ * 1D <- 2/(N-1) sum_q 2D[p,q,r,q] (alpha block), and E = Tr(K 2D) of the new 2D.
+ * Overwrites prob->d1, d2aa, d2ab.  R_aa/R_ab/U_aa/U_ab (device [r^4] each)
+ * receive R and U if not NULL.  E_host and norm2_host (||R||^2 of the input
+ * state, before masking) may be NULL.  Synchronises if either is not NULL. */
+acse_status acse_step(acse_ctx ctx, acse_problem *prob, double eps, const acse_options *opts,
+                      double *R_aa, double *R_ab, double *U_aa, double *U_ab,
+                      double *E_host, double *norm2_host);
+
+/* Human-readable name of a status code (static storage). */
+const char *acse_status_str(acse_status s);
+
+/* Detail of the last failing call on ctx (valid until the next call). */
+const char *acse_last_error(acse_ctx ctx);
+
+/* Number of bytes of device workspace the context holds. */
+int64_t acse_workspace_bytes(acse_ctx ctx);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* ACSE_H */

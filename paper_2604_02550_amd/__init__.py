@@ -1,0 +1,229 @@
+"""Python binding of libacse.so, the MI355X ACSE residual library.
+
+Argument marshalling only: every step of the residual, update and energy runs
+in the HIP kernels behind the C ABI of ``include/acse.h``.  PyTorch provides
+device memory and the stream.  If the shared library is missing the import
+fails; there is no CPU fallback.
+
+    import paper_2604_02550_amd as acse
+    ctx = acse.Context(r_max=50)
+    R_aa, R_ab, norm2 = ctx.residual(h, V, d1, d2aa, d2ab, n_alpha, precision="fp64")
+"""
+import ctypes
+import os
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libacse.so")
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError(f"{LIB_PATH} is not built; run paper_2604_02550_amd/build.py "
+                      "(or __graft_entry__.build())")
+_lib = ctypes.CDLL(LIB_PATH)
+
+FP64, FP32, BF16X3 = 0, 1, 2
+PRECISIONS = {"fp64": FP64, "fp32": FP32, "bf16x3": BF16X3}
+STATUS = {0: "ACSE_OK", 1: "ACSE_ERR_ARG", 2: "ACSE_ERR_SHAPE", 3: "ACSE_ERR_ALIGN",
+          4: "ACSE_ERR_UNSUPPORTED", 5: "ACSE_ERR_NOMEM", 6: "ACSE_ERR_HIP",
+          7: "ACSE_ERR_NONFINITE"}
+
+# Every function declared in include/acse.h.
+EXPORTS = ("acse_create", "acse_destroy", "acse_set_stream", "acse_residual", "acse_update_map",
+           "acse_energy", "acse_step", "acse_status_str", "acse_last_error",
+           "acse_workspace_bytes")
+
+
+class Problem(ctypes.Structure):
+    _fields_ = [("r", ctypes.c_int32), ("n_alpha", ctypes.c_int32), ("n_beta", ctypes.c_int32),
+                ("h", ctypes.c_void_p), ("V", ctypes.c_void_p), ("d1", ctypes.c_void_p),
+                ("d2aa", ctypes.c_void_p), ("d2ab", ctypes.c_void_p)]
+
+
+class Options(ctypes.Structure):
+    _fields_ = [("precision", ctypes.c_int32), ("active", ctypes.c_void_p), ("tile", ctypes.c_int32)]
+
+
+_P = ctypes.c_void_p
+_D = ctypes.POINTER(ctypes.c_double)
+_sig = {
+    "acse_create": (ctypes.c_int, [ctypes.POINTER(_P), ctypes.c_int, _P, ctypes.c_int32]),
+    "acse_destroy": (ctypes.c_int, [_P]),
+    "acse_set_stream": (ctypes.c_int, [_P, _P]),
+    "acse_residual": (ctypes.c_int, [_P, ctypes.POINTER(Problem), ctypes.POINTER(Options), _P, _P, _D]),
+    "acse_update_map": (ctypes.c_int, [_P, ctypes.POINTER(Problem), ctypes.POINTER(Options), _P, _P,
+                                       _P, _P]),
+    "acse_energy": (ctypes.c_int, [_P, ctypes.POINTER(Problem), _D]),
+    "acse_step": (ctypes.c_int, [_P, ctypes.POINTER(Problem), ctypes.c_double,
+                                 ctypes.POINTER(Options), _P, _P, _P, _P, _D, _D]),
+    "acse_status_str": (ctypes.c_char_p, [ctypes.c_int]),
+    "acse_last_error": (ctypes.c_char_p, [_P]),
+    "acse_workspace_bytes": (ctypes.c_int64, [_P]),
+}
+for _name, (_res, _args) in _sig.items():
+    _fn = getattr(_lib, _name)
+    _fn.restype = _res
+    _fn.argtypes = _args
+
+
+class AcseError(RuntimeError):
+    def __init__(self, status, detail):
+        super().__init__(f"{STATUS.get(status, status)}: {detail}")
+        self.status = status
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None else None
+
+
+def _dev(t, device):
+    if not isinstance(t, torch.Tensor):
+        t = torch.as_tensor(t)
+    return t.to(device=device, dtype=torch.float64).contiguous()
+
+
+class Context:
+    """One library context: a device, a stream and workspace for r <= r_max."""
+
+    def __init__(self, r_max, device=0, stream=None):
+        self.device = torch.device("cuda", device) if isinstance(device, int) else torch.device(device)
+        idx = self.device.index or 0
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        h = ctypes.c_void_p()
+        st = _lib.acse_create(ctypes.byref(h), idx, ctypes.c_void_p(self.stream.cuda_stream),
+                              int(r_max))
+        if st != 0:
+            raise AcseError(st, "acse_create failed")
+        self._h = h
+        self.r_max = r_max
+
+    def close(self):
+        if getattr(self, "_h", None):
+            _lib.acse_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    @property
+    def workspace_bytes(self):
+        return int(_lib.acse_workspace_bytes(self._h))
+
+    def _check(self, st):
+        if st != 0:
+            raise AcseError(st, _lib.acse_last_error(self._h).decode())
+
+    def problem(self, h, V, d1, d2aa, d2ab, n_alpha, n_beta=None):
+        """Device copies (float64, contiguous) and the ctypes problem struct."""
+        t = [_dev(x, self.device) for x in (h, V, d1, d2aa, d2ab)]
+        r = t[0].shape[0]
+        prob = Problem(r, int(n_alpha), int(n_alpha if n_beta is None else n_beta),
+                       *[x.data_ptr() for x in t])
+        return prob, t
+
+    @staticmethod
+    def options(precision="fp64", active=None, tile=-1):
+        prec = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
+        keep = None
+        act = None
+        if active is not None:
+            keep = (ctypes.c_uint8 * len(active))(*[1 if a else 0 for a in active])
+            act = ctypes.cast(keep, ctypes.c_void_p)
+        o = Options(prec, act, int(tile))
+        o._keep = keep
+        return o
+
+    def residual_raw(self, prob, opts, R_aa, R_ab, want_norm=True):
+        n2 = ctypes.c_double(0.0)
+        self._check(_lib.acse_residual(self._h, ctypes.byref(prob), ctypes.byref(opts), _ptr(R_aa),
+                                       _ptr(R_ab), ctypes.byref(n2) if want_norm else None))
+        return n2.value
+
+    def residual(self, h, V, d1, d2aa, d2ab, n_alpha, precision="fp64", tile=-1):
+        """R_aa, R_ab (device, float64) and ||R||^2 of Eq. (4)."""
+        prob, keep = self.problem(h, V, d1, d2aa, d2ab, n_alpha)
+        r = prob.r
+        R_aa = torch.empty((r, r, r, r), dtype=torch.float64, device=self.device)
+        R_ab = torch.empty_like(R_aa)
+        n2 = self.residual_raw(prob, self.options(precision, None, tile), R_aa, R_ab)
+        return R_aa, R_ab, n2
+
+    def update_map(self, h, V, d1, d2aa, d2ab, n_alpha, X_aa, X_ab, precision="fp64", tile=-1):
+        """U = 1/2 <[a+a+aa, sum X a+a+aa]> for anti-Hermitian X (Eq. (9))."""
+        prob, keep = self.problem(h, V, d1, d2aa, d2ab, n_alpha)
+        X_aa, X_ab = _dev(X_aa, self.device), _dev(X_ab, self.device)
+        U_aa = torch.empty_like(X_aa)
+        U_ab = torch.empty_like(X_ab)
+        self._check(_lib.acse_update_map(self._h, ctypes.byref(prob),
+                                         ctypes.byref(self.options(precision, None, tile)),
+                                         _ptr(X_aa), _ptr(X_ab), _ptr(U_aa), _ptr(U_ab)))
+        return U_aa, U_ab
+
+    def energy_raw(self, prob):
+        e = ctypes.c_double(0.0)
+        self._check(_lib.acse_energy(self._h, ctypes.byref(prob), ctypes.byref(e)))
+        return e.value
+
+    def energy(self, h, V, d2aa, d2ab, n_alpha):
+        """E = Tr(K 2D) (Eq. (2), Eq. (6))."""
+        r = h.shape[0]
+        prob, keep = self.problem(h, V, torch.zeros(r, r), d2aa, d2ab, n_alpha)
+        return self.energy_raw(prob)
+
+    def step_raw(self, prob, eps, opts, R_aa=None, R_ab=None, U_aa=None, U_ab=None, want=True):
+        e = ctypes.c_double(0.0)
+        n2 = ctypes.c_double(0.0)
+        self._check(_lib.acse_step(self._h, ctypes.byref(prob), float(eps), ctypes.byref(opts),
+                                   _ptr(R_aa), _ptr(R_ab), _ptr(U_aa), _ptr(U_ab),
+                                   ctypes.byref(e) if want else None,
+                                   ctypes.byref(n2) if want else None))
+        return e.value, n2.value
+
+    def step(self, h, V, d1, d2aa, d2ab, n_alpha, eps=1e-3, precision="fp64", active=None,
+             tile=-1, return_ru=False):
+        """One Euler step of Eq. (9) on device copies; returns a dict with the new
+        d1, d2aa, d2ab, the energy after the step and ||R||^2 before it."""
+        prob, t = self.problem(h, V, d1, d2aa, d2ab, n_alpha)
+        r = prob.r
+        extra = {}
+        bufs = [None] * 4
+        if return_ru:
+            bufs = [torch.empty((r, r, r, r), dtype=torch.float64, device=self.device) for _ in range(4)]
+        E, n2 = self.step_raw(prob, eps, self.options(precision, active, tile), *bufs)
+        if return_ru:
+            extra = dict(R_aa=bufs[0], R_ab=bufs[1], U_aa=bufs[2], U_ab=bufs[3])
+        return dict(d1=t[2], d2aa=t[3], d2ab=t[4], energy=E, norm2=n2, **extra)
+
+
+def status_str(code):
+    return _lib.acse_status_str(int(code)).decode()
+
+
+_contexts = {}
+
+
+def context(r, device=0):
+    """A cached context with room for r (grown as needed)."""
+    key = device
+    c = _contexts.get(key)
+    if c is None or c.r_max < r:
+        if c is not None:
+            c.close()
+        c = Context(max(r, 8), device)
+        _contexts[key] = c
+    return c
+
+
+def residual(h, V, d1, d2aa, d2ab, n_alpha, precision="fp64"):
+    return context(h.shape[0]).residual(h, V, d1, d2aa, d2ab, n_alpha, precision)
+
+
+def energy(h, V, d2aa, d2ab, n_alpha):
+    return context(h.shape[0]).energy(h, V, d2aa, d2ab, n_alpha)
+
+
+def step(h, V, d1, d2aa, d2ab, n_alpha, eps=1e-3, precision="fp64", active=None):
+    return context(h.shape[0]).step(h, V, d1, d2aa, d2ab, n_alpha, eps, precision, active)

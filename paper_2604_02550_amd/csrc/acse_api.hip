@@ -1,0 +1,420 @@
+// C ABI of libacse.so (declared in include/acse.h): context, validation and
+// the orchestration of the residual map on the GPU.
+//
+// Residual map F(X) for a two-body tensor X with singlet blocks (A_aa, A_ab)
+// (the antisymmetrised reduced Hamiltonian for the residual of Eq. (4), the
+// masked residual for the update of Eq. (9)), with the Valdemoro 3-RDM of
+// App. C, Eq. (C5) folded in and never formed:
+//
+//   f, t                 O(r^4), O(r^5) contractions of X with gamma and W
+//   H, G2, Bpp = A - G2  one-index transforms and the f terms (pp operand)
+//   Z_aa = Gamma2_aa Bpp_aa^T,  Z_ab = 2 Gamma2_ab Bpp_ab^T        pp GEMMs
+//   P+- = (Xt_aa +- Xt_ab)(W'_a +- W'_b)^T,  E3 = -2 Xt3 W3^T      ph GEMMs
+//   C = 4/3 (gamma x gamma) G2 (separable, two one-index transforms)
+//   S = Z + C - gamma t terms - antisymmetrised particle-hole terms
+//   F = S - S^T (Hermitian X),  F = S + S^T (anti-Hermitian X)
+//
+// The five GEMMs (10 r^6 flops) run as one grouped MFMA launch.
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+
+#include "../../include/acse.h"
+#include "tensor_ops.h"
+
+using namespace acse;
+
+namespace {
+
+struct Workspace {
+  // natural FP64 r^4 arrays
+  double *Aaa, *Aab, *Waa, *Wab, *Haa, *Hab, *G2aa, *G2ab, *T1, *Caa, *Cab;
+  double *Zaa, *Zab, *Pp, *Pm, *E3, *Saa, *Sab;
+  double *Raa, *Rab, *Maa, *Mab, *Uaa, *Uab, *Naa, *Nab;
+  // GEMM operand buffers (sized for FP64, reused by the narrower formats)
+  char *op[10];
+  // small arrays
+  double *fpart, *f, *tpart, *t, *partial, *scal;
+};
+
+}  // namespace
+
+struct acse_ctx_s {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  int r_max = 0;
+  std::string err;
+  void *base = nullptr;
+  int64_t bytes = 0;
+  int64_t op_bytes = 0;
+  Workspace ws{};
+};
+
+namespace {
+
+constexpr int kNat = 26;  // natural r^4 arrays in Workspace
+
+acse_status fail(acse_ctx c, acse_status s, const std::string &msg) {
+  if (c) c->err = msg;
+  return s;
+}
+
+#define HIP_TRY(ctx, expr)                                                                   \
+  do {                                                                                       \
+    hipError_t e_ = (expr);                                                                  \
+    if (e_ != hipSuccess)                                                                    \
+      return fail(ctx, ACSE_ERR_HIP, std::string(#expr) + ": " + hipGetErrorString(e_));     \
+  } while (0)
+
+bool aligned16(const void *p) { return (reinterpret_cast<uintptr_t>(p) & 15u) == 0; }
+
+int64_t op_rows(int r) { return round_up((int64_t)r * r, kRowPad); }
+int64_t op_ld(int r) { return round_up((int64_t)r * r, kKPad); }
+
+OperandRef operand(const Workspace &w, int idx, GemmPrec prec, int r) {
+  OperandRef o{w.op[idx], nullptr};
+  if (prec == GEMM_BF16X3) o.lo = w.op[idx] + op_rows(r) * op_ld(r) * 2;
+  return o;
+}
+enum { OP_DAA, OP_DAB, OP_BAA, OP_BAB, OP_LP, OP_LM, OP_L3, OP_RP, OP_RM, OP_R3 };
+
+acse_status validate(acse_ctx c, const acse_problem *p, const acse_options *o, bool need_d1 = true) {
+  if (!c) return ACSE_ERR_ARG;
+  if (!p) return fail(c, ACSE_ERR_ARG, "problem is NULL");
+  if (p->r < 2 || p->r > c->r_max)
+    return fail(c, ACSE_ERR_SHAPE, "r = " + std::to_string(p->r) + " outside [2, r_max = " +
+                                       std::to_string(c->r_max) + "]");
+  const int N = p->n_alpha + p->n_beta;
+  if (p->n_alpha < 0 || p->n_beta < 0 || N < 2 || p->n_alpha > p->r || p->n_beta > p->r)
+    return fail(c, ACSE_ERR_SHAPE, "electron counts must satisfy N >= 2 and n_sigma <= r");
+  if (p->n_alpha != p->n_beta)
+    return fail(c, ACSE_ERR_UNSUPPORTED, "only n_alpha == n_beta (singlet blocks) is built");
+  if (!p->h || !p->V || !p->d2aa || !p->d2ab || (need_d1 && !p->d1))
+    return fail(c, ACSE_ERR_ARG, "a problem pointer is NULL");
+  if (!aligned16(p->h) || !aligned16(p->V) || !aligned16(p->d2aa) || !aligned16(p->d2ab) ||
+      (need_d1 && !aligned16(p->d1)))
+    return fail(c, ACSE_ERR_ALIGN, "problem arrays must be 16-byte aligned");
+  if (o) {
+    if (o->precision < ACSE_FP64 || o->precision > ACSE_BF16X3)
+      return fail(c, ACSE_ERR_ARG, "unknown precision");
+    if (o->tile < -1 || o->tile >= gemm_num_tiles(GEMM_F64))
+      return fail(c, ACSE_ERR_ARG, "tile configuration out of range");
+  }
+  return ACSE_OK;
+}
+
+acse_status check_out(acse_ctx c, const void *p, const char *name) {
+  if (!p) return fail(c, ACSE_ERR_ARG, std::string(name) + " is NULL");
+  if (!aligned16(p)) return fail(c, ACSE_ERR_ALIGN, std::string(name) + " must be 16-byte aligned");
+  return ACSE_OK;
+}
+
+GemmPrec prec_of(const acse_options *o) {
+  if (!o) return GEMM_F64;
+  return o->precision == ACSE_FP32 ? GEMM_F32 : o->precision == ACSE_BF16X3 ? GEMM_BF16X3 : GEMM_F64;
+}
+
+// Operands that depend only on (gamma, 2D): W natural, the ph B operands and
+// the pp A operands.
+acse_status prep_rdm_operands(acse_ctx c, const acse_problem *p, GemmPrec prec) {
+  const int r = p->r;
+  const int ld = (int)op_ld(r);
+  Workspace &w = c->ws;
+  HIP_TRY(c, launch_w_natural(r, p->d1, p->d2aa, p->d2ab, w.Waa, w.Wab, c->stream));
+  HIP_TRY(c, launch_w_ph(prec, r, ld, p->d1, p->d2aa, p->d2ab, operand(w, OP_RP, prec, r),
+                         operand(w, OP_RM, prec, r), operand(w, OP_R3, prec, r), c->stream));
+  HIP_TRY(c, launch_d_operand(prec, r, ld, p->d2aa, p->d2ab, operand(w, OP_DAA, prec, r),
+                              operand(w, OP_DAB, prec, r), c->stream));
+  return ACSE_OK;
+}
+
+ModeArgs mode_base(int r, const double *g) {
+  ModeArgs m{};
+  m.r = r;
+  m.g = g;
+  m.c1 = 1.0;
+  m.c2 = 0.0;
+  m.alpha = 1.0;
+  m.adiv = 1;
+  return m;
+}
+
+// F(X) into (Oaa, Oab); sigma = -1 for Hermitian X, +1 for anti-Hermitian X.
+// If Maa is not null it receives the active-masked copy.  The norm
+// 2||O_aa||^2 + 4||O_ab||^2 lands in ws.scal[slot].
+acse_status run_map(acse_ctx c, const acse_problem *p, GemmPrec prec, int cfg, const double *Xaa,
+                    const double *Xab, double sigma, double *Oaa, double *Oab,
+                    const ActiveBits &act, double *Maa, double *Mab, int slot) {
+  const int r = p->r;
+  const int64_t r2 = (int64_t)r * r, r3 = r2 * r;
+  const int ld = (int)op_ld(r);
+  const double *g = p->d1;
+  Workspace &w = c->ws;
+  hipStream_t s = c->stream;
+
+  HIP_TRY(c, launch_f(r, Xaa, Xab, g, w.fpart, w.f, s));
+  HIP_TRY(c, launch_t(r, w.Waa, Xaa, w.Wab, Xab, w.tpart, w.t, s));
+
+  // H[k,l,(r,s)] = sum_p X[k,p,(r,s)] g[p,l]
+  for (int b = 0; b < 2; ++b) {
+    ModeArgs m = mode_base(r, g);
+    m.A = r; m.Bn = r2; m.in1 = b ? Xab : Xaa; m.transpose_m = 1;
+    m.so1 = r3; m.so0 = 0; m.sx = r2; m.sb = 1; m.out_cols_fast = 1;
+    HIP_TRY(c, launch_mode(GEMM_F64, m, OperandRef{b ? w.Hab : w.Haa, nullptr}, s));
+  }
+  HIP_TRY(c, launch_g2(prec, r, ld, Xaa, Xab, w.Haa, w.Hab, w.f, w.G2aa, w.G2ab,
+                       operand(w, OP_BAA, prec, r), operand(w, OP_BAB, prec, r), s));
+  // C^T[k,l,i,j] = 4/3 sum_rs g_ir g_js G2[k,l,r,s]
+  for (int b = 0; b < 2; ++b) {
+    ModeArgs m1 = mode_base(r, g);  // T1[k,l,r,j] = sum_s g[j,s] G2[k,l,r,s]
+    m1.A = r3; m1.Bn = 1; m1.in1 = b ? w.G2ab : w.G2aa;
+    m1.so1 = r; m1.so0 = 0; m1.sx = 1; m1.sb = 0; m1.out_cols_fast = 0;
+    HIP_TRY(c, launch_mode(GEMM_F64, m1, OperandRef{w.T1, nullptr}, s));
+    ModeArgs m2 = mode_base(r, g);  // C^T[k,l,i,j] = 4/3 sum_r g[i,r] T1[k,l,r,j]
+    m2.A = r2; m2.Bn = r; m2.in1 = w.T1; m2.alpha = 4.0 / 3.0;
+    m2.so1 = r2; m2.so0 = 0; m2.sx = r; m2.sb = 1; m2.out_cols_fast = 1;
+    HIP_TRY(c, launch_mode(GEMM_F64, m2, OperandRef{b ? w.Cab : w.Caa, nullptr}, s));
+  }
+  // ph A operands: L+-[(k,i),(p,s)] = sum_r g[i,r] (X_aa +- X_ab)[k,p,r,s]
+  for (int q : {OP_LP, OP_LM, OP_L3})
+    HIP_TRY(c, launch_zero_kpad(prec, r, ld, operand(w, q, prec, r), s));
+  for (int b = 0; b < 2; ++b) {
+    ModeArgs m = mode_base(r, g);
+    m.A = r2; m.Bn = r; m.in1 = Xaa; m.in2 = Xab; m.c2 = b ? -1.0 : 1.0;
+    m.adiv = r; m.so1 = (int64_t)r * ld; m.so0 = r; m.sx = ld; m.sb = 1; m.out_cols_fast = 1;
+    HIP_TRY(c, launch_mode(prec, m, operand(w, b ? OP_LM : OP_LP, prec, r), s));
+  }
+  {  // L3[(k,j),(p,s)] = sum_r g[j,r] X_ab[k,p,s,r]
+    ModeArgs m = mode_base(r, g);
+    m.A = r3; m.Bn = 1; m.in1 = Xab;
+    m.adiv = r2; m.so1 = (int64_t)r * ld; m.so0 = 1; m.sx = ld; m.sb = 0; m.out_cols_fast = 1;
+    HIP_TRY(c, launch_mode(prec, m, operand(w, OP_L3, prec, r), s));
+  }
+
+  // grouped GEMM: 2 pp + 3 ph products
+  GemmBatch batch{};
+  batch.count = 5;
+  auto set = [&](int q, int ia, int ib, double alpha, double *C, int64_t sm1, int64_t sm0,
+                 int64_t sn1, int64_t sn0) {
+    GemmProb &P = batch.p[q];
+    OperandRef a = operand(w, ia, prec, r), bb = operand(w, ib, prec, r);
+    P.A = a.hi; P.A2 = a.lo; P.B = bb.hi; P.B2 = bb.lo;
+    P.C = C; P.alpha = alpha;
+    P.M = (int)r2; P.N = (int)r2; P.Kp = ld; P.ld = ld; P.rdiv = r;
+    P.sm1 = sm1; P.sm0 = sm0; P.sn1 = sn1; P.sn0 = sn0;
+    P.ksplit = 1; P.kchunk = ld; P.accumulate = 0;
+  };
+  set(0, OP_DAA, OP_BAA, 2.0, w.Zaa, r3, r2, r, 1);   // rows (i,j), cols (k,l)
+  set(1, OP_DAB, OP_BAB, 4.0, w.Zab, r3, r2, r, 1);
+  set(2, OP_LP, OP_RP, 1.0, w.Pp, r, r3, r2, 1);      // rows (k,i), cols (j,l) -> [i,j,k,l]
+  set(3, OP_LM, OP_RM, 1.0, w.Pm, r, r3, r2, 1);
+  set(4, OP_L3, OP_R3, -2.0, w.E3, r, r2, r3, 1);     // rows (k,j), cols (i,l) -> [i,j,k,l]
+  const int use_cfg = cfg >= 0 ? cfg : gemm_default_cfg(prec, (int)r2, (int)r2);
+  HIP_TRY(c, gemm_launch(prec, use_cfg, batch, s));
+
+  HIP_TRY(c, launch_assemble(r, g, w.t, w.Zaa, w.Zab, w.Pp, w.Pm, w.E3, w.Saa, w.Sab, s));
+  HIP_TRY(c, launch_finish(r, sigma, w.Saa, w.Sab, w.Caa, w.Cab, Oaa, Oab, act, Maa, Mab,
+                           w.partial, w.scal + slot, s));
+  return ACSE_OK;
+}
+
+ActiveBits make_bits(const acse_options *o, int r, bool *any) {
+  ActiveBits b{};
+  *any = false;
+  if (o && o->active) {
+    for (int q = 0; q < r; ++q)
+      if (o->active[q]) { b.w[q >> 6] |= 1ull << (q & 63); *any = true; }
+  }
+  return b;
+}
+
+acse_status fetch_scalars(acse_ctx c, double *norm2_host, double *E_host) {
+  if (!norm2_host && !E_host) return ACSE_OK;
+  double host[2] = {0.0, 0.0};
+  HIP_TRY(c, hipMemcpyAsync(host, c->ws.scal, 2 * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+  HIP_TRY(c, hipStreamSynchronize(c->stream));
+  if (norm2_host) {
+    *norm2_host = host[0];
+    if (!std::isfinite(host[0])) return fail(c, ACSE_ERR_NONFINITE, "||R||^2 is not finite");
+  }
+  if (E_host) {
+    *E_host = host[1];
+    if (!std::isfinite(host[1])) return fail(c, ACSE_ERR_NONFINITE, "energy is not finite");
+  }
+  return ACSE_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *acse_status_str(acse_status s) {
+  switch (s) {
+    case ACSE_OK: return "ACSE_OK";
+    case ACSE_ERR_ARG: return "ACSE_ERR_ARG";
+    case ACSE_ERR_SHAPE: return "ACSE_ERR_SHAPE";
+    case ACSE_ERR_ALIGN: return "ACSE_ERR_ALIGN";
+    case ACSE_ERR_UNSUPPORTED: return "ACSE_ERR_UNSUPPORTED";
+    case ACSE_ERR_NOMEM: return "ACSE_ERR_NOMEM";
+    case ACSE_ERR_HIP: return "ACSE_ERR_HIP";
+    case ACSE_ERR_NONFINITE: return "ACSE_ERR_NONFINITE";
+  }
+  return "ACSE_ERR_UNKNOWN";
+}
+
+const char *acse_last_error(acse_ctx ctx) { return ctx ? ctx->err.c_str() : "null context"; }
+
+int64_t acse_workspace_bytes(acse_ctx ctx) { return ctx ? ctx->bytes : -1; }
+
+acse_status acse_create(acse_ctx *out, int device, void *hip_stream, int32_t r_max) {
+  if (!out) return ACSE_ERR_ARG;
+  *out = nullptr;
+  if (r_max < 2 || r_max > kModeMaxR) return ACSE_ERR_SHAPE;
+  acse_ctx c = new (std::nothrow) acse_ctx_s();
+  if (!c) return ACSE_ERR_NOMEM;
+  c->device = device;
+  c->stream = static_cast<hipStream_t>(hip_stream);
+  c->r_max = r_max;
+  if (hipSetDevice(device) != hipSuccess) { delete c; return ACSE_ERR_HIP; }
+  const int64_t n4 = (int64_t)r_max * r_max * r_max * r_max;
+  const int64_t r2 = (int64_t)r_max * r_max;
+  const int64_t nat = round_up(n4 * 8, 256);
+  const int64_t opb = round_up(op_rows(r_max) * op_ld(r_max) * 8, 256);
+  const int64_t small = round_up((int64_t)r_max * r2 * 8, 256) + round_up(r2 * 8, 256) +
+                        round_up((int64_t)t_partial_blocks() * r2 * 8, 256) + round_up(r2 * 8, 256) +
+                        round_up(finish_partials(r_max) * 8, 256) + 256;
+  c->bytes = kNat * nat + 10 * opb + small;
+  c->op_bytes = opb;
+  if (hipMalloc(&c->base, c->bytes) != hipSuccess) {
+    (void)hipGetLastError();
+    delete c;
+    return ACSE_ERR_NOMEM;
+  }
+  char *p = static_cast<char *>(c->base);
+  Workspace &w = c->ws;
+  double **nats[kNat] = {&w.Aaa, &w.Aab, &w.Waa, &w.Wab, &w.Haa, &w.Hab, &w.G2aa, &w.G2ab, &w.T1,
+                         &w.Caa, &w.Cab, &w.Zaa, &w.Zab, &w.Pp,  &w.Pm,  &w.E3,  &w.Saa,  &w.Sab,
+                         &w.Raa, &w.Rab, &w.Maa, &w.Mab, &w.Uaa, &w.Uab, &w.Naa, &w.Nab};
+  for (int q = 0; q < kNat; ++q) { *nats[q] = reinterpret_cast<double *>(p); p += nat; }
+  for (int q = 0; q < 10; ++q) { w.op[q] = p; p += opb; }
+  w.fpart = reinterpret_cast<double *>(p); p += round_up((int64_t)r_max * r2 * 8, 256);
+  w.f = reinterpret_cast<double *>(p); p += round_up(r2 * 8, 256);
+  w.tpart = reinterpret_cast<double *>(p); p += round_up((int64_t)t_partial_blocks() * r2 * 8, 256);
+  w.t = reinterpret_cast<double *>(p); p += round_up(r2 * 8, 256);
+  w.partial = reinterpret_cast<double *>(p); p += round_up(finish_partials(r_max) * 8, 256);
+  w.scal = reinterpret_cast<double *>(p);
+  // Operand padding rows are read by full tiles: give every byte a defined value once.
+  if (launch_fill((10 * opb) / 8, 0.0, reinterpret_cast<double *>(w.op[0]), c->stream) != hipSuccess ||
+      hipStreamSynchronize(c->stream) != hipSuccess) {
+    (void)hipFree(c->base);
+    delete c;
+    return ACSE_ERR_HIP;
+  }
+  *out = c;
+  return ACSE_OK;
+}
+
+acse_status acse_destroy(acse_ctx ctx) {
+  if (!ctx) return ACSE_ERR_ARG;
+  (void)hipSetDevice(ctx->device);
+  (void)hipStreamSynchronize(ctx->stream);
+  (void)hipFree(ctx->base);
+  delete ctx;
+  return ACSE_OK;
+}
+
+acse_status acse_set_stream(acse_ctx ctx, void *hip_stream) {
+  if (!ctx) return ACSE_ERR_ARG;
+  ctx->stream = static_cast<hipStream_t>(hip_stream);
+  return ACSE_OK;
+}
+
+acse_status acse_residual(acse_ctx ctx, const acse_problem *prob, const acse_options *opts,
+                          double *R_aa, double *R_ab, double *norm2_host) {
+  acse_status st = validate(ctx, prob, opts);
+  if (st != ACSE_OK) return st;
+  if ((st = check_out(ctx, R_aa, "R_aa")) != ACSE_OK) return st;
+  if ((st = check_out(ctx, R_ab, "R_ab")) != ACSE_OK) return st;
+  HIP_TRY(ctx, hipSetDevice(ctx->device));
+  const GemmPrec prec = prec_of(opts);
+  const int cfg = opts ? opts->tile : -1;
+  if ((st = prep_rdm_operands(ctx, prob, prec)) != ACSE_OK) return st;
+  const int N = prob->n_alpha + prob->n_beta;
+  HIP_TRY(ctx, launch_fold(prob->r, N, prob->h, prob->V, ctx->ws.Aaa, ctx->ws.Aab, ctx->stream));
+  const ActiveBits none{};
+  if ((st = run_map(ctx, prob, prec, cfg, ctx->ws.Aaa, ctx->ws.Aab, -1.0, R_aa, R_ab, none, nullptr,
+                    nullptr, 0)) != ACSE_OK)
+    return st;
+  return fetch_scalars(ctx, norm2_host, nullptr);
+}
+
+acse_status acse_update_map(acse_ctx ctx, const acse_problem *prob, const acse_options *opts,
+                            const double *X_aa, const double *X_ab, double *U_aa, double *U_ab) {
+  acse_status st = validate(ctx, prob, opts);
+  if (st != ACSE_OK) return st;
+  if ((st = check_out(ctx, X_aa, "X_aa")) != ACSE_OK) return st;
+  if ((st = check_out(ctx, X_ab, "X_ab")) != ACSE_OK) return st;
+  if ((st = check_out(ctx, U_aa, "U_aa")) != ACSE_OK) return st;
+  if ((st = check_out(ctx, U_ab, "U_ab")) != ACSE_OK) return st;
+  HIP_TRY(ctx, hipSetDevice(ctx->device));
+  const GemmPrec prec = prec_of(opts);
+  if ((st = prep_rdm_operands(ctx, prob, prec)) != ACSE_OK) return st;
+  const ActiveBits none{};
+  return run_map(ctx, prob, prec, opts ? opts->tile : -1, X_aa, X_ab, +1.0, U_aa, U_ab, none,
+                 nullptr, nullptr, 2);
+}
+
+acse_status acse_energy(acse_ctx ctx, const acse_problem *prob, double *E_host) {
+  acse_status st = validate(ctx, prob, nullptr, false);
+  if (st != ACSE_OK) return st;
+  if (!E_host) return fail(ctx, ACSE_ERR_ARG, "E_host is NULL");
+  HIP_TRY(ctx, hipSetDevice(ctx->device));
+  const int N = prob->n_alpha + prob->n_beta;
+  HIP_TRY(ctx, launch_energy(prob->r, N, prob->h, prob->V, prob->d2aa, prob->d2ab, ctx->ws.partial,
+                             ctx->ws.scal + 1, ctx->stream));
+  return fetch_scalars(ctx, nullptr, E_host);
+}
+
+acse_status acse_step(acse_ctx ctx, acse_problem *prob, double eps, const acse_options *opts,
+                      double *R_aa, double *R_ab, double *U_aa, double *U_ab, double *E_host,
+                      double *norm2_host) {
+  acse_status st = validate(ctx, prob, opts);
+  if (st != ACSE_OK) return st;
+  if (!std::isfinite(eps)) return fail(ctx, ACSE_ERR_ARG, "eps is not finite");
+  for (const void *q : {static_cast<const void *>(R_aa), static_cast<const void *>(R_ab),
+                        static_cast<const void *>(U_aa), static_cast<const void *>(U_ab)})
+    if (q && !aligned16(q)) return fail(ctx, ACSE_ERR_ALIGN, "output arrays must be 16-byte aligned");
+  HIP_TRY(ctx, hipSetDevice(ctx->device));
+  Workspace &w = ctx->ws;
+  hipStream_t s = ctx->stream;
+  const int r = prob->r;
+  const int N = prob->n_alpha + prob->n_beta;
+  const GemmPrec prec = prec_of(opts);
+  const int cfg = opts ? opts->tile : -1;
+  double *Raa = R_aa ? R_aa : w.Raa, *Rab = R_ab ? R_ab : w.Rab;
+  double *Uaa = U_aa ? U_aa : w.Uaa, *Uab = U_ab ? U_ab : w.Uab;
+  bool masked = false;
+  const ActiveBits act = make_bits(opts, r, &masked);
+
+  if ((st = prep_rdm_operands(ctx, prob, prec)) != ACSE_OK) return st;
+  HIP_TRY(ctx, launch_fold(r, N, prob->h, prob->V, w.Aaa, w.Aab, s));
+  // R = F(K), ||R||^2 -> scal[0], masked copy -> M
+  if ((st = run_map(ctx, prob, prec, cfg, w.Aaa, w.Aab, -1.0, Raa, Rab, act,
+                    masked ? w.Maa : nullptr, masked ? w.Mab : nullptr, 0)) != ACSE_OK)
+    return st;
+  // U = F(R_m)
+  if ((st = run_map(ctx, prob, prec, cfg, masked ? w.Maa : Raa, masked ? w.Mab : Rab, +1.0, Uaa, Uab,
+                    ActiveBits{}, nullptr, nullptr, 2)) != ACSE_OK)
+    return st;
+  // 2D <- 2D + eps U, trace restoration, 1-RDM contraction, energy (FP64)
+  HIP_TRY(ctx, launch_traces(r, prob->d2aa, prob->d2ab, w.scal + 4, s));
+  HIP_TRY(ctx, launch_axpy2(r, eps, prob->d2aa, prob->d2ab, Uaa, Uab, w.Naa, w.Nab, s));
+  HIP_TRY(ctx, launch_traces(r, w.Naa, w.Nab, w.scal + 6, s));
+  HIP_TRY(ctx, launch_rescale(r, w.scal + 4, w.Naa, w.Nab, prob->d2aa, prob->d2ab, s));
+  HIP_TRY(ctx, launch_contract_1rdm(r, N, prob->d2aa, prob->d2ab, prob->d1, s));
+  HIP_TRY(ctx, launch_energy(r, N, prob->h, prob->V, prob->d2aa, prob->d2ab, w.partial, w.scal + 1, s));
+  return fetch_scalars(ctx, norm2_host, E_host);
+}
+
+}  // extern "C"

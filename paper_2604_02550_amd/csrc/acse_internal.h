@@ -1,0 +1,58 @@
+// Internal declarations shared by the HIP translation units of libacse.so.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <hip/hip_bf16.h>
+#include <cstdint>
+
+namespace acse {
+
+// ---------------------------------------------------------------------------
+// Grouped NT GEMM:  C_g[m, n] = alpha_g * sum_k A_g[m, k] * B_g[n, k]
+//
+// Operands are row-major with leading dimension ld (elements), rows padded to
+// the tile height and K padded (with zeros) to a multiple of the K tile, so
+// the kernel loads without bounds checks.  The store of element (m, n) goes to
+//   C[(m / rdiv) * sm1 + (m % rdiv) * sm0 + (n / rdiv) * sn1 + (n % rdiv) * sn0]
+// which lets the pair-index products write directly in any 4-index order.
+// With ksplit > 1 each K chunk writes its own partial block at
+// C + split * split_stride (natural layout m * N + n).
+// ---------------------------------------------------------------------------
+enum GemmPrec { GEMM_F64 = 0, GEMM_F32 = 1, GEMM_BF16X3 = 2 };
+
+struct GemmProb {
+  const void *A;      // plane 0 (hi for bf16x3)
+  const void *B;
+  const void *A2;     // lo plane (bf16x3 only)
+  const void *B2;
+  double *C;
+  double alpha;
+  int64_t sm1, sm0, sn1, sn0, split_stride;
+  int M, N, Kp, ld;   // Kp: padded K (multiple of the K tile); ld >= Kp
+  int rdiv;
+  int ksplit, kchunk; // K chunks (kchunk multiple of the K tile)
+  int tiles_m, tiles_n, tile_begin;
+  int accumulate;     // 1: C += alpha * AB^T
+};
+
+constexpr int kMaxGemmProbs = 6;
+struct GemmBatch {
+  GemmProb p[kMaxGemmProbs];
+  int count;
+  int total_tiles;
+};
+
+// Tile configurations (index = options.tile; -1 picks by size).
+struct GemmTileInfo { int bm, bn, bk; };
+int gemm_num_tiles(GemmPrec prec);
+GemmTileInfo gemm_tile_info(GemmPrec prec, int cfg);
+int gemm_default_cfg(GemmPrec prec, int M, int N);
+// Row padding and K padding every operand buffer must provide.
+constexpr int kRowPad = 256;
+constexpr int kKPad = 64;
+
+// Fills tiles_m/tiles_n/tile_begin/total_tiles and launches.
+hipError_t gemm_launch(GemmPrec prec, int cfg, GemmBatch &batch, hipStream_t s);
+
+inline int64_t round_up(int64_t x, int64_t m) { return (x + m - 1) / m * m; }
+
+}  // namespace acse

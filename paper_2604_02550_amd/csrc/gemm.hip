@@ -1,0 +1,272 @@
+// LDS-tiled MFMA NT GEMMs for gfx950 (FP64, FP32, split-BF16).
+//
+// Every O(r^6) contraction of the residual is a pair-index product
+// C[(a,b),(c,d)] = sum_(e,f) A[(a,b),(e,f)] B[(c,d),(e,f)] with r^2 x r^2
+// operands; this file holds the one kernel that runs them all.
+//
+// Structure: a workgroup of 4 wavefronts (2 x 2) owns a BM x BN output tile;
+// each wave owns a (BM/2) x (BN/2) sub-tile made of 16 x 16 MFMA blocks.  The
+// K loop stages BK-wide slabs of A and B through LDS with register
+// double-buffering (the next slab's global loads are in flight while the
+// current slab feeds the MFMAs).  LDS rows are padded so that the 16 rows a
+// half-wave reads for one MFMA operand fall in distinct banks.
+#include "acse_internal.h"
+
+namespace acse {
+
+typedef double d4 __attribute__((ext_vector_type(4)));
+typedef float f4 __attribute__((ext_vector_type(4)));
+typedef __bf16 bf8 __attribute__((ext_vector_type(8)));
+
+struct TrF64 {
+  using T = double;
+  using Acc = d4;
+  static constexpr int NPLANE = 1, VEC = 2, PAD = 2, KSTEP = 4;
+};
+struct TrF32 {
+  using T = float;
+  using Acc = f4;
+  static constexpr int NPLANE = 1, VEC = 4, PAD = 4, KSTEP = 4;
+};
+struct TrBF16x3 {
+  using T = __bf16;
+  using Acc = f4;
+  static constexpr int NPLANE = 2, VEC = 8, PAD = 8, KSTEP = 32;
+};
+
+template <class Tr>
+__device__ inline typename Tr::Acc acc_zero() {
+  typename Tr::Acc a;
+  a[0] = 0; a[1] = 0; a[2] = 0; a[3] = 0;
+  return a;
+}
+
+template <class Tr, int BM, int BN, int BK>
+__global__ void __launch_bounds__(256)
+gemm_nt_kernel(const GemmBatch batch) {
+  using T = typename Tr::T;
+  using Acc = typename Tr::Acc;
+  constexpr int NT = 256;
+  constexpr int WTM = BM / 2, WTN = BN / 2;
+  constexpr int FM = WTM / 16, FN = WTN / 16;
+  constexpr int LDK = BK + Tr::PAD;
+  constexpr int NP = Tr::NPLANE;
+  constexpr int VEC = Tr::VEC;
+  constexpr int CH_A = BM * BK / VEC / NT;   // 16-byte chunks per thread per plane
+  constexpr int CH_B = BN * BK / VEC / NT;
+  static_assert(CH_A * VEC * NT == BM * BK, "A tile must split evenly");
+  static_assert(CH_B * VEC * NT == BN * BK, "B tile must split evenly");
+  static_assert(BK % Tr::KSTEP == 0, "K tile must hold whole MFMA steps");
+
+  __shared__ __attribute__((aligned(16))) T As[2][NP][BM * LDK];
+  __shared__ __attribute__((aligned(16))) T Bs[2][NP][BN * LDK];
+
+  // --- which problem / tile / K chunk --------------------------------------
+  const int bid = blockIdx.x;
+  int g = 0;
+#pragma unroll
+  for (int q = 1; q < kMaxGemmProbs; ++q)
+    if (q < batch.count && bid >= batch.p[q].tile_begin) g = q;
+  const GemmProb &P = batch.p[g];
+  int local = bid - P.tile_begin;
+  const int per_split = P.tiles_m * P.tiles_n;
+  const int split = local / per_split;
+  local -= split * per_split;
+  const int tm = local / P.tiles_n;
+  const int tn = local - tm * P.tiles_n;
+  const int m0 = tm * BM, n0 = tn * BN;
+  const int kbeg = split * P.kchunk;
+  const int kend = min(P.Kp, kbeg + P.kchunk);
+  const int nk = (kend - kbeg) / BK;
+
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wave = tid >> 6;
+  const int wm0 = (wave >> 1) * WTM, wn0 = (wave & 1) * WTN;
+
+  const T *Ap[2] = {static_cast<const T *>(P.A), static_cast<const T *>(NP > 1 ? P.A2 : P.A)};
+  const T *Bp[2] = {static_cast<const T *>(P.B), static_cast<const T *>(NP > 1 ? P.B2 : P.B)};
+  const int64_t ld = P.ld;
+
+  // 16-byte global chunks -> registers
+  typedef int32_t i4 __attribute__((ext_vector_type(4)));
+  i4 ra[NP][CH_A], rb[NP][CH_B];
+  auto gload = [&](int k0) {
+#pragma unroll
+    for (int p = 0; p < NP; ++p) {
+#pragma unroll
+      for (int c = 0; c < CH_A; ++c) {
+        const int ch = tid + c * NT;
+        const int row = ch / (BK / VEC), kc = (ch % (BK / VEC)) * VEC;
+        ra[p][c] = *reinterpret_cast<const i4 *>(Ap[p] + (int64_t)(m0 + row) * ld + k0 + kc);
+      }
+#pragma unroll
+      for (int c = 0; c < CH_B; ++c) {
+        const int ch = tid + c * NT;
+        const int row = ch / (BK / VEC), kc = (ch % (BK / VEC)) * VEC;
+        rb[p][c] = *reinterpret_cast<const i4 *>(Bp[p] + (int64_t)(n0 + row) * ld + k0 + kc);
+      }
+    }
+  };
+  auto lstore = [&](int buf) {
+#pragma unroll
+    for (int p = 0; p < NP; ++p) {
+#pragma unroll
+      for (int c = 0; c < CH_A; ++c) {
+        const int ch = tid + c * NT;
+        const int row = ch / (BK / VEC), kc = (ch % (BK / VEC)) * VEC;
+        *reinterpret_cast<i4 *>(&As[buf][p][row * LDK + kc]) = ra[p][c];
+      }
+#pragma unroll
+      for (int c = 0; c < CH_B; ++c) {
+        const int ch = tid + c * NT;
+        const int row = ch / (BK / VEC), kc = (ch % (BK / VEC)) * VEC;
+        *reinterpret_cast<i4 *>(&Bs[buf][p][row * LDK + kc]) = rb[p][c];
+      }
+    }
+  };
+
+  Acc acc[FM][FN];
+#pragma unroll
+  for (int i = 0; i < FM; ++i)
+#pragma unroll
+    for (int j = 0; j < FN; ++j) acc[i][j] = acc_zero<Tr>();
+
+  const int lrow = lane & 15;
+  const int lk = lane >> 4;
+
+  if (nk > 0) {
+    gload(kbeg);
+    lstore(0);
+    __syncthreads();
+  }
+  for (int kt = 0; kt < nk; ++kt) {
+    const int buf = kt & 1;
+    if (kt + 1 < nk) gload(kbeg + (kt + 1) * BK);
+#pragma unroll
+    for (int kk = 0; kk < BK; kk += Tr::KSTEP) {
+      if constexpr (NP == 1) {
+        T a[FM], b[FN];
+#pragma unroll
+        for (int i = 0; i < FM; ++i) a[i] = As[buf][0][(wm0 + i * 16 + lrow) * LDK + kk + lk];
+#pragma unroll
+        for (int j = 0; j < FN; ++j) b[j] = Bs[buf][0][(wn0 + j * 16 + lrow) * LDK + kk + lk];
+#pragma unroll
+        for (int i = 0; i < FM; ++i)
+#pragma unroll
+          for (int j = 0; j < FN; ++j) {
+            if constexpr (sizeof(T) == 8)
+              acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[i], b[j], acc[i][j], 0, 0, 0);
+            else
+              acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[i], b[j], acc[i][j], 0, 0, 0);
+          }
+      } else {
+        bf8 ah[FM], al[FM], bh[FN], bl[FN];
+#pragma unroll
+        for (int i = 0; i < FM; ++i) {
+          const int o = (wm0 + i * 16 + lrow) * LDK + kk + lk * 8;
+          ah[i] = *reinterpret_cast<const bf8 *>(&As[buf][0][o]);
+          al[i] = *reinterpret_cast<const bf8 *>(&As[buf][1][o]);
+        }
+#pragma unroll
+        for (int j = 0; j < FN; ++j) {
+          const int o = (wn0 + j * 16 + lrow) * LDK + kk + lk * 8;
+          bh[j] = *reinterpret_cast<const bf8 *>(&Bs[buf][0][o]);
+          bl[j] = *reinterpret_cast<const bf8 *>(&Bs[buf][1][o]);
+        }
+#pragma unroll
+        for (int i = 0; i < FM; ++i)
+#pragma unroll
+          for (int j = 0; j < FN; ++j) {
+            acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al[i], bh[j], acc[i][j], 0, 0, 0);
+            acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[i], bl[j], acc[i][j], 0, 0, 0);
+            acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[i], bh[j], acc[i][j], 0, 0, 0);
+          }
+      }
+    }
+    if (kt + 1 < nk) lstore(buf ^ 1);
+    __syncthreads();
+  }
+
+  // --- epilogue: (m, n) -> permuted 4-index address ---------------------------
+  const double alpha = P.alpha;
+  double *C = P.C + (P.ksplit > 1 ? split * P.split_stride : 0);
+  const int rdiv = P.rdiv;
+#pragma unroll
+  for (int i = 0; i < FM; ++i) {
+#pragma unroll
+    for (int j = 0; j < FN; ++j) {
+      const int n = n0 + wn0 + j * 16 + lrow;
+      if (n >= P.N) continue;
+      const int64_t noff = (int64_t)(n / rdiv) * P.sn1 + (int64_t)(n % rdiv) * P.sn0;
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        // accumulator item v of lane l is row (l/16) + 4v for the FP64 MFMA and
+        // row 4(l/16) + v for the FP32 / BF16 ones; the column is l % 16
+        const int m = m0 + wm0 + i * 16 + (sizeof(T) == 8 ? lk + 4 * v : lk * 4 + v);
+        if (m >= P.M) continue;
+        const int64_t off = (int64_t)(m / rdiv) * P.sm1 + (int64_t)(m % rdiv) * P.sm0 + noff;
+        const double val = alpha * (double)acc[i][j][v];
+        if (P.accumulate) C[off] += val; else C[off] = val;
+      }
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Configurations
+// ---------------------------------------------------------------------------
+namespace {
+struct Cfg { int bm, bn, bk; };
+constexpr Cfg kCfgF64[] = {{128, 128, 16}, {64, 64, 16}, {128, 64, 16}};
+constexpr Cfg kCfgF32[] = {{128, 128, 32}, {64, 64, 32}, {128, 64, 32}};
+constexpr Cfg kCfgBF[] = {{128, 128, 32}, {64, 64, 32}, {128, 64, 32}};
+
+template <class Tr, int BM, int BN, int BK>
+hipError_t launch_one(const GemmBatch &b, hipStream_t s) {
+  hipLaunchKernelGGL((gemm_nt_kernel<Tr, BM, BN, BK>), dim3(b.total_tiles), dim3(256), 0, s, b);
+  return hipGetLastError();
+}
+}  // namespace
+
+int gemm_num_tiles(GemmPrec) { return 3; }
+
+GemmTileInfo gemm_tile_info(GemmPrec prec, int cfg) {
+  const Cfg *t = prec == GEMM_F64 ? kCfgF64 : prec == GEMM_F32 ? kCfgF32 : kCfgBF;
+  return {t[cfg].bm, t[cfg].bn, t[cfg].bk};
+}
+
+int gemm_default_cfg(GemmPrec prec, int M, int N) {
+  // Large tiles once there are enough of them to fill 256 CUs twice over.
+  const int64_t big = ((M + 127) / 128) * (int64_t)((N + 127) / 128);
+  (void)prec;
+  return big >= 512 ? 0 : 1;
+}
+
+hipError_t gemm_launch(GemmPrec prec, int cfg, GemmBatch &b, hipStream_t s) {
+  const GemmTileInfo ti = gemm_tile_info(prec, cfg);
+  int total = 0;
+  for (int q = 0; q < b.count; ++q) {
+    GemmProb &p = b.p[q];
+    p.tiles_m = (p.M + ti.bm - 1) / ti.bm;
+    p.tiles_n = (p.N + ti.bn - 1) / ti.bn;
+    if (p.ksplit < 1) p.ksplit = 1;
+    if (p.kchunk <= 0) p.kchunk = p.Kp;
+    p.tile_begin = total;
+    total += p.tiles_m * p.tiles_n * p.ksplit;
+  }
+  b.total_tiles = total;
+  if (total == 0) return hipSuccess;
+#define ACSE_GEMM_CASE(TR, CFGS)                                                          \
+  switch (cfg) {                                                                          \
+    case 0: return launch_one<TR, CFGS[0].bm, CFGS[0].bn, CFGS[0].bk>(b, s);               \
+    case 1: return launch_one<TR, CFGS[1].bm, CFGS[1].bn, CFGS[1].bk>(b, s);               \
+    default: return launch_one<TR, CFGS[2].bm, CFGS[2].bn, CFGS[2].bk>(b, s);              \
+  }
+  if (prec == GEMM_F64) { ACSE_GEMM_CASE(TrF64, kCfgF64) }
+  if (prec == GEMM_F32) { ACSE_GEMM_CASE(TrF32, kCfgF32) }
+  ACSE_GEMM_CASE(TrBF16x3, kCfgBF)
+#undef ACSE_GEMM_CASE
+}
+
+}  // namespace acse

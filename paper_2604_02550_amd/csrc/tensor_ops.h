@@ -1,0 +1,71 @@
+// Launchers of the O(r^4) / O(r^5) kernels (tensor_ops.hip).
+#pragma once
+#include "acse_internal.h"
+
+namespace acse {
+
+// A GEMM operand buffer: one plane (FP64/FP32) or a hi and a lo plane (BF16x3).
+struct OperandRef {
+  void *hi;
+  void *lo;
+};
+
+// out[a, x, b] = alpha * sum_y M(x, y) (c1 in1 + c2 in2)[a, y, b]   (see tensor_ops.hip)
+struct ModeArgs {
+  int r;
+  int64_t A, Bn;
+  const double *in1;
+  const double *in2;  // may be null
+  double c1, c2;
+  const double *g;    // r x r
+  int transpose_m;    // M(x,y) = g[y][x] if set
+  double alpha;
+  int64_t adiv, so1, so0, sx, sb;
+  int out_cols_fast;  // output contiguous along (a,b) columns rather than along x
+};
+constexpr int kModeMaxR = 96;
+size_t mode_lds_bytes(int r);
+
+hipError_t launch_fold(int r, int N, const double *h, const double *V, double *Aaa, double *Aab,
+                       hipStream_t s);
+hipError_t launch_w_natural(int r, const double *g, const double *d2aa, const double *d2ab,
+                            double *Waa, double *Wab, hipStream_t s);
+hipError_t launch_w_ph(GemmPrec prec, int r, int ld, const double *g, const double *d2aa,
+                       const double *d2ab, const OperandRef &Rp, const OperandRef &Rm,
+                       const OperandRef &R3, hipStream_t s);
+hipError_t launch_d_operand(GemmPrec prec, int r, int ld, const double *d2aa, const double *d2ab,
+                            const OperandRef &Daa, const OperandRef &Dab, hipStream_t s);
+hipError_t launch_zero_kpad(GemmPrec prec, int r, int ld, const OperandRef &o, hipStream_t s);
+hipError_t launch_f(int r, const double *Aaa, const double *Aab, const double *g, double *part,
+                    double *f, hipStream_t s);
+hipError_t launch_mode(GemmPrec prec, const ModeArgs &m, const OperandRef &out, hipStream_t s);
+hipError_t launch_g2(GemmPrec prec, int r, int ld, const double *Aaa, const double *Aab,
+                     const double *Haa, const double *Hab, const double *f, double *G2aa,
+                     double *G2ab, const OperandRef &Baa, const OperandRef &Bab, hipStream_t s);
+hipError_t launch_assemble(int r, const double *g, const double *t, const double *Zaa,
+                           const double *Zab, const double *Pp, const double *Pm, const double *E3,
+                           double *Saa, double *Sab, hipStream_t s);
+struct ActiveBits { uint64_t w[4]; };  // per-orbital active flags, r <= 256
+hipError_t launch_finish(int r, double sigma, const double *Saa, const double *Sab,
+                         const double *Caa, const double *Cab, double *Oaa, double *Oab,
+                         const ActiveBits &active, double *Maa, double *Mab, double *partial,
+                         double *sum_out, hipStream_t s);
+int64_t finish_partials(int r);
+hipError_t launch_t_reduce(int r, int nparts, const double *part, double *t, hipStream_t s);
+int t_partial_blocks();
+// t[j,k] = sum_{prs} (W_aa[j,p,r,s] A_aa[k,p,r,s] + 2 W_ab[j,p,r,s] A_ab[k,p,r,s])
+hipError_t launch_t(int r, const double *Waa, const double *Aaa, const double *Wab,
+                    const double *Aab, double *part, double *t, hipStream_t s);
+hipError_t launch_energy(int r, int N, const double *h, const double *V, const double *d2aa,
+                         const double *d2ab, double *partial, double *E_out, hipStream_t s);
+hipError_t launch_traces(int r, const double *d2aa, const double *d2ab, double *traces,
+                         hipStream_t s);
+hipError_t launch_axpy2(int r, double eps, const double *aa, const double *ab, const double *Uaa,
+                        const double *Uab, double *oaa, double *oab, hipStream_t s);
+hipError_t launch_rescale(int r, const double *traces, const double *naa, const double *nab,
+                          double *d2aa, double *d2ab, hipStream_t s);
+hipError_t launch_contract_1rdm(int r, int N, const double *d2aa, const double *d2ab, double *g,
+                                hipStream_t s);
+hipError_t launch_fill(int64_t n, double v, double *p, hipStream_t s);
+
+}  // namespace acse

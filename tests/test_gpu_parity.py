@@ -1,0 +1,168 @@
+"""GPU parity: the HIP path through the C ABI against the CPU FP64 oracle.
+
+FP64 bar: normwise relative error <= 1e-10 and max |diff| <= 1e-10 max|ref| for
+every array; scalars relative 1e-10.  Sizes span several GEMM tiles with
+ragged tails (r^2 = 36, 100, 169, 900 against 64/128 tiles).
+"""
+import numpy as np
+import pytest
+
+from oracle import fermion as fm
+from oracle import step as ost
+from synth import generators as gen
+
+pytestmark = pytest.mark.gpu
+
+TOL64 = 1e-10
+
+
+@pytest.fixture(scope="module")
+def acse():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.fail("no GPU visible")
+    import paper_2604_02550_amd as acse
+    return acse
+
+
+@pytest.fixture(scope="module")
+def ctx(acse):
+    return acse.Context(r_max=50)
+
+
+def rel(a, b):
+    a = np.asarray(a)
+    b = np.asarray(b)
+    return float(np.linalg.norm((a - b).ravel()) / max(np.linalg.norm(b.ravel()), 1e-300))
+
+
+def maxrel(a, b):
+    return float(np.abs(np.asarray(a) - np.asarray(b)).max() / max(np.abs(b).max(), 1e-300))
+
+
+def cpu(t):
+    return t.detach().cpu().numpy()
+
+
+def tiny_problem(seed=0):
+    rng = np.random.default_rng(seed)
+    h, V = gen.hamiltonian(rng, 4, 6)
+    p = fm.fci_singlet_problem(h, V, 4)
+    return dict(r=4, N=4, h=h, V=V, gamma=p["gamma"], d2aa=p["d2aa"], d2ab=p["d2ab"],
+                e_fci=p["energy"])
+
+
+PROBLEMS = {
+    "tiny_fci": lambda: tiny_problem(0),
+    "r6": lambda: gen.problem(6, 4, 12, seed=1),
+    "r10": lambda: gen.problem(10, 6, 20, seed=2),
+    "r13": lambda: gen.problem(13, 8, 26, seed=3),
+}
+
+
+@pytest.mark.parametrize("name", list(PROBLEMS))
+def test_residual_fp64(ctx, name):
+    p = PROBLEMS[name]()
+    print(f"[residual_fp64] {name} r={p['r']}", flush=True)
+    raa, rab, n2 = ost.residual(p["h"], p["V"], p["N"], p["gamma"], p["d2aa"], p["d2ab"])
+    Raa, Rab, gn2 = ctx.residual(p["h"], p["V"], p["gamma"], p["d2aa"], p["d2ab"], p["N"] // 2)
+    Raa, Rab = cpu(Raa), cpu(Rab)
+    assert rel(Raa, raa) < TOL64 and maxrel(Raa, raa) < TOL64
+    assert rel(Rab, rab) < TOL64 and maxrel(Rab, rab) < TOL64
+    assert abs(gn2 - n2) <= TOL64 * n2
+
+
+@pytest.mark.parametrize("name", list(PROBLEMS))
+def test_energy_fp64(ctx, name):
+    p = PROBLEMS[name]()
+    e = ost.energy(p["h"], p["V"], p["N"], p["d2aa"], p["d2ab"])
+    ge = ctx.energy(p["h"], p["V"], p["d2aa"], p["d2ab"], p["N"] // 2)
+    assert abs(ge - e) <= TOL64 * max(1.0, abs(e))
+    if "e_fci" in p:
+        assert abs(ge - p["e_fci"]) < 1e-10
+
+
+@pytest.mark.parametrize("name,active", [("tiny_fci", None), ("r10", None), ("r13", "mid")])
+def test_step_fp64(ctx, name, active):
+    p = PROBLEMS[name]()
+    r = p["r"]
+    act = None
+    if active == "mid":
+        act = np.zeros(r, bool)
+        act[max(0, p["N"] // 4 - 2): p["N"] // 4 + 3] = True
+    print(f"[step_fp64] {name} r={r} active={act}", flush=True)
+    o = ost.step(p["h"], p["V"], p["N"], p["gamma"], p["d2aa"], p["d2ab"], 1e-3, active=act)
+    g = ctx.step(p["h"], p["V"], p["gamma"], p["d2aa"], p["d2ab"], p["N"] // 2, eps=1e-3,
+                 active=act, return_ru=True)
+    for key in ("R_aa", "R_ab", "U_aa", "U_ab", "d2aa", "d2ab"):
+        assert rel(cpu(g[key]), o[key]) < TOL64, key
+        assert maxrel(cpu(g[key]), o[key]) < TOL64, key
+    assert maxrel(cpu(g["d1"]), o["gamma"]) < TOL64
+    assert abs(g["energy"] - o["energy"]) <= TOL64 * max(1.0, abs(o["energy"]))
+    assert abs(g["norm2"] - o["norm2"]) <= TOL64 * o["norm2"]
+
+
+def test_update_map_fp64(ctx):
+    p = PROBLEMS["r10"]()
+    o = ost.step(p["h"], p["V"], p["N"], p["gamma"], p["d2aa"], p["d2ab"], 1e-3)
+    Uaa, Uab = ctx.update_map(p["h"], p["V"], p["gamma"], p["d2aa"], p["d2ab"], p["N"] // 2,
+                              o["R_aa"], o["R_ab"])
+    assert rel(cpu(Uaa), o["U_aa"]) < TOL64 and rel(cpu(Uab), o["U_ab"]) < TOL64
+
+
+@pytest.mark.parametrize("tile", [0, 1, 2])
+def test_every_tile_config(ctx, tile):
+    p = PROBLEMS["r13"]()
+    raa, rab, n2 = ost.residual(p["h"], p["V"], p["N"], p["gamma"], p["d2aa"], p["d2ab"])
+    Raa, Rab, gn2 = ctx.residual(p["h"], p["V"], p["gamma"], p["d2aa"], p["d2ab"], p["N"] // 2,
+                                 tile=tile)
+    assert rel(cpu(Raa), raa) < TOL64 and rel(cpu(Rab), rab) < TOL64
+
+
+def test_deterministic(ctx):
+    p = PROBLEMS["r10"]()
+    a = ctx.residual(p["h"], p["V"], p["gamma"], p["d2aa"], p["d2ab"], p["N"] // 2)
+    b = ctx.residual(p["h"], p["V"], p["gamma"], p["d2aa"], p["d2ab"], p["N"] // 2)
+    assert bool((a[0] == b[0]).all()) and bool((a[1] == b[1]).all()) and a[2] == b[2]
+
+
+@pytest.fixture(scope="module")
+def r30():
+    p = gen.named("r30")
+    o = ost.step(p["h"], p["V"], p["N"], p["gamma"], p["d2aa"], p["d2ab"], 1e-3)
+    return p, o
+
+
+def test_r30_step_fp64(ctx, r30):
+    p, o = r30
+    print("[r30_step_fp64]", flush=True)
+    g = ctx.step(p["h"], p["V"], p["gamma"], p["d2aa"], p["d2ab"], p["N"] // 2, eps=1e-3,
+                 return_ru=True)
+    for key in ("R_aa", "R_ab", "U_aa", "U_ab", "d2aa", "d2ab"):
+        assert rel(cpu(g[key]), o[key]) < TOL64, key
+    assert abs(g["energy"] - o["energy"]) <= TOL64 * abs(o["energy"])
+    assert abs(g["norm2"] - o["norm2"]) <= TOL64 * o["norm2"]
+
+
+# Per-result relative (normwise) tolerances of the mixed modes, and the bound on
+# the error of the one-step energy change relative to that change.
+MIXED_TOL = {"fp32": dict(R=1e-5, U=1e-5, dE_rel=1e-6),
+             "bf16x3": dict(R=5e-5, U=5e-5, dE_rel=1e-5)}
+
+
+@pytest.mark.parametrize("precision", ["fp32", "bf16x3"])
+def test_r30_mixed_precision_errors(ctx, r30, precision):
+    """Mixed precision: per-result errors against the FP64 oracle (stated tolerances)."""
+    p, o = r30
+    g = ctx.step(p["h"], p["V"], p["gamma"], p["d2aa"], p["d2ab"], p["N"] // 2, eps=1e-3,
+                 precision=precision, return_ru=True)
+    errs = {k: rel(cpu(g[k]), o[k]) for k in ("R_aa", "R_ab", "U_aa", "U_ab", "d2aa", "d2ab")}
+    de = abs(g["energy"] - o["energy"])
+    de_rel = de / abs(o["energy"] - o["energy0"])
+    dn = abs(g["norm2"] - o["norm2"]) / o["norm2"]
+    print(f"[mixed] {precision} rel errors {errs} |dE|={de:.3e} |dE|/|E1-E0|={de_rel:.3e} "
+          f"rel d||R||^2={dn:.3e}", flush=True)
+    tol = MIXED_TOL[precision]
+    assert errs["R_aa"] < tol["R"] and errs["R_ab"] < tol["R"]
+    assert errs["U_aa"] < tol["U"] and errs["U_ab"] < tol["U"]
+    assert de_rel < tol["dE_rel"]
