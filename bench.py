@@ -1,0 +1,214 @@
+"""Benchmark of the ACSE residual hot path on one MI355X.
+
+A step is one pass of the whole hot path on the r = 50, N = 30 synthetic
+workload (seed 0): the residual R of Eq. (4) with the Valdemoro 3-RDM, its
+norm, the update map U = F(R), the Euler update of the 2-RDM blocks, trace
+restoration, the 1-RDM contraction and the energy (one ``acse_step`` call).
+Each step starts from the same input state: the 1-/2-RDM blocks are restored
+on the device from a pristine copy inside the timed region (one r^4 device copy
+per block, negligible next to the contractions).
+
+Prints one JSON line.  ``value`` = residual evaluations per second = steps per
+second (one residual per step; the update map, step and energy are inside the
+same timed step).  The residual-only rate of the same kernels is reported
+beside it, and the FP32 / split-BF16 modes are timed and checked against the
+stored FP64 oracle values.
+
+    python bench.py [--steps K] [--warmup W] [--modes fp64,fp32,bf16x3] [--no-cpu-baseline]
+"""
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK_TFLOPS = {"fp64": 78.6, "fp32": 157.3, "bf16x3": 2516.6}
+GOLDEN = os.path.join(ROOT, "tests", "golden", "r50_step.json")
+TRAFFIC = os.path.join(ROOT, "profiles", "gemm_traffic_r50.json")
+GEMM_SRC = os.path.join(ROOT, "paper_2604_02550_amd", "csrc", "gemm.hip")
+
+
+def gemm_flops(r):
+    """Algorithmic flops of one grouped GEMM launch: five r^2 x r^2 x r^2 products."""
+    return 5 * 2 * r ** 6
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="r50")
+    ap.add_argument("--modes", default="fp64,fp32,bf16x3")
+    ap.add_argument("--eps", type=float, default=1e-3)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--calibrate-copy-mib", type=int, default=0,
+                    help="run one plain device copy of this many MiB (counter calibration)")
+    return ap.parse_args()
+
+
+def src_hash():
+    with open(GEMM_SRC, "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()[:16]
+
+
+def main():
+    args = parse()
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}, WORLD_SIZE {world}); "
+              "the multi-GPU path is not built.", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import paper_2604_02550_amd as acse
+    from synth import generators as gen
+
+    dev = torch.device("cuda", 0)
+    p = gen.named(args.workload)
+    r, N = p["r"], p["N"]
+    na = N // 2
+    ctx = acse.Context(r_max=r, device=0)
+    stream = ctx.stream
+    h = torch.as_tensor(p["h"], device=dev).contiguous()
+    V = torch.as_tensor(p["V"], device=dev).contiguous()
+    pristine = [torch.as_tensor(p[k], device=dev).contiguous() for k in ("gamma", "d2aa", "d2ab")]
+    work = [t.clone() for t in pristine]
+    prob = acse.Problem(r, na, na, h.data_ptr(), V.data_ptr(), *[t.data_ptr() for t in work])
+    R = [torch.empty((r, r, r, r), dtype=torch.float64, device=dev) for _ in range(2)]
+    U = [torch.empty((r, r, r, r), dtype=torch.float64, device=dev) for _ in range(2)]
+
+    if args.calibrate_copy_mib:
+        n = args.calibrate_copy_mib * 2 ** 20 // 8
+        a = torch.ones(n, dtype=torch.float64, device=dev)
+        b = torch.empty_like(a)
+        b.copy_(a)
+        torch.cuda.synchronize()
+        del a, b
+
+    golden = json.load(open(GOLDEN)) if os.path.exists(GOLDEN) and args.workload == "r50" else None
+
+    def restore():
+        for w, q in zip(work, pristine):
+            w.copy_(q)
+
+    results = {}
+    for mode in args.modes.split(","):
+        opts = acse.Context.options(mode)
+        # warmup
+        for _ in range(args.warmup):
+            restore()
+            ctx.step_raw(prob, args.eps, opts, want=False)
+        torch.cuda.synchronize()
+        ctx.profile(True)
+        start = torch.cuda.Event(enable_timing=True)
+        stop = torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        start.record(stream)
+        for _ in range(args.steps):
+            restore()
+            ctx.step_raw(prob, args.eps, opts, R[0], R[1], U[0], U[1], want=False)
+        stop.record(stream)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        ms = start.elapsed_time(stop) / args.steps
+        prof = ctx.profile_read()
+        ctx.profile(False)
+        gemm_ms, gemm_n = prof["gemm"]
+        # residual-only rate of the same kernels
+        res_steps = max(args.steps, 5)
+        for _ in range(2):
+            ctx.residual_raw(prob, opts, R[0], R[1], want_norm=False)
+        torch.cuda.synchronize()
+        s2 = torch.cuda.Event(enable_timing=True)
+        e2 = torch.cuda.Event(enable_timing=True)
+        restore()
+        s2.record(stream)
+        for _ in range(res_steps):
+            ctx.residual_raw(prob, opts, R[0], R[1], want_norm=False)
+        e2.record(stream)
+        torch.cuda.synchronize()
+        res_ms = s2.elapsed_time(e2) / res_steps
+        # one checked step against the stored oracle values
+        restore()
+        E1, n2 = ctx.step_raw(prob, args.eps, opts, R[0], R[1], U[0], U[1])
+        err = None
+        if golden is not None:
+            idx = [tuple(t) for t in golden["index"]]
+            got = {k: v.cpu().numpy() for k, v in
+                   (("R_aa", R[0]), ("R_ab", R[1]), ("U_aa", U[0]), ("U_ab", U[1]))}
+            err = dict(
+                dE=abs(E1 - golden["energy1"]),
+                dE_rel_to_step=abs(E1 - golden["energy1"]) / abs(golden["energy1"] - golden["energy0"]),
+                norm2_rel=abs(n2 - golden["norm2"]) / golden["norm2"],
+            )
+            for k in got:
+                ref = np.array(golden["samples"][k])
+                val = np.array([got[k][t] for t in idx])
+                err[f"{k}_sample_rel"] = float(np.abs(val - ref).max() / np.abs(ref).max())
+                err[f"{k}_norm_rel"] = abs(float(np.linalg.norm(got[k])) - golden["norms"][k]) / golden["norms"][k]
+        gemm_avg = gemm_ms / max(gemm_n, 1)
+        achieved = gemm_flops(r) / (gemm_avg * 1e-3) / 1e12
+        results[mode] = dict(
+            ms_per_step=ms, steps_per_s=1e3 / ms, wall_s=wall, residual_ms=res_ms,
+            residual_evals_per_s=1e3 / res_ms,
+            gemm_avg_ms=gemm_avg, gemm_launches=gemm_n, gemm_tflops=achieved,
+            stage_ms_per_step={k: v[0] / args.steps for k, v in prof.items()},
+            useful_tflops_step=2 * gemm_flops(r) / (ms * 1e-3) / 1e12,
+            error_vs_oracle=err, energy1=E1, norm2=n2,
+        )
+
+    head = args.modes.split(",")[0]
+    hr = results[head]
+    traffic = None
+    if os.path.exists(TRAFFIC):
+        t = json.load(open(TRAFFIC))
+        if t.get("gemm_src_sha256_16") == src_hash() and t.get("precision") == head:
+            traffic = t.get("bytes_per_launch")
+    line = {
+        "metric": "ACSE residual evals/s + TFLOP/s at r=50: FP64 vs mixed at |dE|<1e-7 Eh",
+        "value": hr["steps_per_s"],
+        "unit": "residual evals/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": hr["ms_per_step"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": {"fp64": "f64", "fp32": "f32", "bf16x3": "bf16x3"}[head],
+        "data": "synthetic",
+        "config": {"workload": f"{args.workload}: r={r} spatial orbitals, N={N}, singlet "
+                               "alpha-alpha/alpha-beta blocks, one acse_step (eps=1e-3) per step",
+                   "r": r, "N": N, "precision": head},
+        "tflops": hr["useful_tflops_step"],
+        "roofline": {"bound": "mfma", "achieved": hr["gemm_tflops"], "peak": PEAK_TFLOPS[head],
+                     "unit": "TFLOP/s", "frac": hr["gemm_tflops"] / PEAK_TFLOPS[head],
+                     "traffic": traffic,
+                     "kernel": "grouped pair-index GEMM (5 x r^2 x r^2 x r^2 per launch)"},
+        "residual_only_evals_per_s": hr["residual_evals_per_s"],
+        "modes": results,
+    }
+    if not args.no_cpu_baseline:
+        import torch as _t
+        from oracle import step as ost
+        threads = _t.get_num_threads()
+        t0 = time.perf_counter()
+        ost.residual(p["h"], p["V"], p["N"], p["gamma"], p["d2aa"], p["d2ab"])
+        dt = time.perf_counter() - t0
+        line["cpu_baseline"] = {"value": 1.0 / dt, "unit": "residual evals/s", "cores": threads,
+                                "kind": "oracle",
+                                "sample": f"one FP64 oracle residual at r={r}, N={N} (spin-orbital "
+                                          f"factorised form, {dt:.1f} s)"}
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -134,6 +134,24 @@ acse_status acse_step(acse_ctx ctx, acse_problem *prob, double eps, const acse_o
                       double *R_aa, double *R_ab, double *U_aa, double *U_ab,
                       double *E_host, double *norm2_host);
 
+/* Stage timing with HIP events recorded on the context's stream.  Stages:
+ *   0  RDM-side operands (W = Gamma2 - 2/3 Gamma1^Gamma1 and its layouts)
+ *   1  fold of the reduced Hamiltonian (Eq. (2))
+ *   2  O(r^4)/O(r^5) transforms feeding the contractions
+ *   3  grouped pair-index GEMM (the five O(r^6) contractions of one map)
+ *   4  assembly, (ij)<->(kl) exchange and the FP64 norm
+ *   5  step tail: axpy, trace restoration, 1-RDM contraction, energy
+ * acse_profile_enable(ctx, 1) clears the totals and starts recording;
+ * acse_profile_read synchronises the stream and returns the totals (ms and
+ * number of timed intervals per stage) since the last enable. */
+#define ACSE_NUM_STAGES 6
+typedef struct {
+  double ms[ACSE_NUM_STAGES];
+  int64_t count[ACSE_NUM_STAGES];
+} acse_profile_data;
+acse_status acse_profile_enable(acse_ctx ctx, int32_t enable);
+acse_status acse_profile_read(acse_ctx ctx, acse_profile_data *out);
+
 /* Human-readable name of a status code (static storage). */
 const char *acse_status_str(acse_status s);
 

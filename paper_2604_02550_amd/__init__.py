@@ -31,13 +31,19 @@ STATUS = {0: "ACSE_OK", 1: "ACSE_ERR_ARG", 2: "ACSE_ERR_SHAPE", 3: "ACSE_ERR_ALI
 # Every function declared in include/acse.h.
 EXPORTS = ("acse_create", "acse_destroy", "acse_set_stream", "acse_residual", "acse_update_map",
            "acse_energy", "acse_step", "acse_status_str", "acse_last_error",
-           "acse_workspace_bytes")
+           "acse_workspace_bytes", "acse_profile_enable", "acse_profile_read")
+NUM_STAGES = 6
+STAGES = ("rdm_operands", "fold", "transforms", "gemm", "assembly", "step_tail")
 
 
 class Problem(ctypes.Structure):
     _fields_ = [("r", ctypes.c_int32), ("n_alpha", ctypes.c_int32), ("n_beta", ctypes.c_int32),
                 ("h", ctypes.c_void_p), ("V", ctypes.c_void_p), ("d1", ctypes.c_void_p),
                 ("d2aa", ctypes.c_void_p), ("d2ab", ctypes.c_void_p)]
+
+
+class ProfileData(ctypes.Structure):
+    _fields_ = [("ms", ctypes.c_double * NUM_STAGES), ("count", ctypes.c_int64 * NUM_STAGES)]
 
 
 class Options(ctypes.Structure):
@@ -59,6 +65,8 @@ _sig = {
     "acse_status_str": (ctypes.c_char_p, [ctypes.c_int]),
     "acse_last_error": (ctypes.c_char_p, [_P]),
     "acse_workspace_bytes": (ctypes.c_int64, [_P]),
+    "acse_profile_enable": (ctypes.c_int, [_P, ctypes.c_int32]),
+    "acse_profile_read": (ctypes.c_int, [_P, ctypes.POINTER(ProfileData)]),
 }
 for _name, (_res, _args) in _sig.items():
     _fn = getattr(_lib, _name)
@@ -111,6 +119,16 @@ class Context:
     @property
     def workspace_bytes(self):
         return int(_lib.acse_workspace_bytes(self._h))
+
+    def profile(self, enable=True):
+        """Start (clearing totals) or stop HIP-event timing of the library stages."""
+        self._check(_lib.acse_profile_enable(self._h, 1 if enable else 0))
+
+    def profile_read(self):
+        """{stage: (total ms, intervals)} since the last profile(True); synchronises."""
+        d = ProfileData()
+        self._check(_lib.acse_profile_read(self._h, ctypes.byref(d)))
+        return {STAGES[i]: (d.ms[i], d.count[i]) for i in range(NUM_STAGES)}
 
     def _check(self, st):
         if st != 0:

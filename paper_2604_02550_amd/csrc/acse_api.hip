@@ -19,6 +19,7 @@
 #include <cstdio>
 #include <cstring>
 #include <string>
+#include <vector>
 
 #include "../../include/acse.h"
 #include "tensor_ops.h"
@@ -49,6 +50,13 @@ struct acse_ctx_s {
   int64_t bytes = 0;
   int64_t op_bytes = 0;
   Workspace ws{};
+  // stage timing
+  bool profiling = false;
+  struct Rec { int stage; hipEvent_t a, b; };
+  std::vector<Rec> recs;
+  std::vector<hipEvent_t> pool;
+  double ms[ACSE_NUM_STAGES] = {};
+  int64_t count[ACSE_NUM_STAGES] = {};
 };
 
 namespace {
@@ -66,6 +74,31 @@ acse_status fail(acse_ctx c, acse_status s, const std::string &msg) {
     if (e_ != hipSuccess)                                                                    \
       return fail(ctx, ACSE_ERR_HIP, std::string(#expr) + ": " + hipGetErrorString(e_));     \
   } while (0)
+
+// Records one event pair around a stage when profiling is on.
+struct StageTimer {
+  acse_ctx c;
+  int stage;
+  hipEvent_t b = nullptr;
+  StageTimer(acse_ctx c_, int stage_) : c(c_), stage(stage_) {
+    if (!c->profiling) return;
+    hipEvent_t a = take();
+    b = take();
+    if (a && b) {
+      (void)hipEventRecord(a, c->stream);
+      c->recs.push_back({stage, a, b});
+    }
+  }
+  ~StageTimer() {
+    if (c->profiling && b) (void)hipEventRecord(b, c->stream);
+  }
+  hipEvent_t take() {
+    if (!c->pool.empty()) { hipEvent_t e = c->pool.back(); c->pool.pop_back(); return e; }
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    return e;
+  }
+};
 
 bool aligned16(const void *p) { return (reinterpret_cast<uintptr_t>(p) & 15u) == 0; }
 
@@ -121,6 +154,7 @@ acse_status prep_rdm_operands(acse_ctx c, const acse_problem *p, GemmPrec prec) 
   const int r = p->r;
   const int ld = (int)op_ld(r);
   Workspace &w = c->ws;
+  StageTimer timer(c, 0);
   HIP_TRY(c, launch_w_natural(r, p->d1, p->d2aa, p->d2ab, w.Waa, w.Wab, c->stream));
   HIP_TRY(c, launch_w_ph(prec, r, ld, p->d1, p->d2aa, p->d2ab, operand(w, OP_RP, prec, r),
                          operand(w, OP_RM, prec, r), operand(w, OP_R3, prec, r), c->stream));
@@ -153,45 +187,47 @@ acse_status run_map(acse_ctx c, const acse_problem *p, GemmPrec prec, int cfg, c
   Workspace &w = c->ws;
   hipStream_t s = c->stream;
 
-  HIP_TRY(c, launch_f(r, Xaa, Xab, g, w.fpart, w.f, s));
-  HIP_TRY(c, launch_t(r, w.Waa, Xaa, w.Wab, Xab, w.tpart, w.t, s));
+  {
+    StageTimer t2(c, 2);
+    HIP_TRY(c, launch_f(r, Xaa, Xab, g, w.fpart, w.f, s));
+    HIP_TRY(c, launch_t(r, w.Waa, Xaa, w.Wab, Xab, w.tpart, w.t, s));
 
-  // H[k,l,(r,s)] = sum_p X[k,p,(r,s)] g[p,l]
-  for (int b = 0; b < 2; ++b) {
-    ModeArgs m = mode_base(r, g);
-    m.A = r; m.Bn = r2; m.in1 = b ? Xab : Xaa; m.transpose_m = 1;
-    m.so1 = r3; m.so0 = 0; m.sx = r2; m.sb = 1; m.out_cols_fast = 1;
-    HIP_TRY(c, launch_mode(GEMM_F64, m, OperandRef{b ? w.Hab : w.Haa, nullptr}, s));
+    // H[k,l,(r,s)] = sum_p X[k,p,(r,s)] g[p,l]
+    for (int b = 0; b < 2; ++b) {
+      ModeArgs m = mode_base(r, g);
+      m.A = r; m.Bn = r2; m.in1 = b ? Xab : Xaa; m.transpose_m = 1;
+      m.so1 = r3; m.so0 = 0; m.sx = r2; m.sb = 1; m.out_cols_fast = 1;
+      HIP_TRY(c, launch_mode(GEMM_F64, m, OperandRef{b ? w.Hab : w.Haa, nullptr}, s));
+    }
+    HIP_TRY(c, launch_g2(prec, r, ld, Xaa, Xab, w.Haa, w.Hab, w.f, w.G2aa, w.G2ab,
+                         operand(w, OP_BAA, prec, r), operand(w, OP_BAB, prec, r), s));
+    // C^T[k,l,i,j] = 4/3 sum_rs g_ir g_js G2[k,l,r,s]
+    for (int b = 0; b < 2; ++b) {
+      ModeArgs m1 = mode_base(r, g);  // T1[k,l,r,j] = sum_s g[j,s] G2[k,l,r,s]
+      m1.A = r3; m1.Bn = 1; m1.in1 = b ? w.G2ab : w.G2aa;
+      m1.so1 = r; m1.so0 = 0; m1.sx = 1; m1.sb = 0; m1.out_cols_fast = 0;
+      HIP_TRY(c, launch_mode(GEMM_F64, m1, OperandRef{w.T1, nullptr}, s));
+      ModeArgs m2 = mode_base(r, g);  // C^T[k,l,i,j] = 4/3 sum_r g[i,r] T1[k,l,r,j]
+      m2.A = r2; m2.Bn = r; m2.in1 = w.T1; m2.alpha = 4.0 / 3.0;
+      m2.so1 = r2; m2.so0 = 0; m2.sx = r; m2.sb = 1; m2.out_cols_fast = 1;
+      HIP_TRY(c, launch_mode(GEMM_F64, m2, OperandRef{b ? w.Cab : w.Caa, nullptr}, s));
+    }
+    // ph A operands: L+-[(k,i),(p,s)] = sum_r g[i,r] (X_aa +- X_ab)[k,p,r,s]
+    for (int q : {OP_LP, OP_LM, OP_L3})
+      HIP_TRY(c, launch_zero_kpad(prec, r, ld, operand(w, q, prec, r), s));
+    for (int b = 0; b < 2; ++b) {
+      ModeArgs m = mode_base(r, g);
+      m.A = r2; m.Bn = r; m.in1 = Xaa; m.in2 = Xab; m.c2 = b ? -1.0 : 1.0;
+      m.adiv = r; m.so1 = (int64_t)r * ld; m.so0 = r; m.sx = ld; m.sb = 1; m.out_cols_fast = 1;
+      HIP_TRY(c, launch_mode(prec, m, operand(w, b ? OP_LM : OP_LP, prec, r), s));
+    }
+    {  // L3[(k,j),(p,s)] = sum_r g[j,r] X_ab[k,p,s,r]
+      ModeArgs m = mode_base(r, g);
+      m.A = r3; m.Bn = 1; m.in1 = Xab;
+      m.adiv = r2; m.so1 = (int64_t)r * ld; m.so0 = 1; m.sx = ld; m.sb = 0; m.out_cols_fast = 1;
+      HIP_TRY(c, launch_mode(prec, m, operand(w, OP_L3, prec, r), s));
+    }
   }
-  HIP_TRY(c, launch_g2(prec, r, ld, Xaa, Xab, w.Haa, w.Hab, w.f, w.G2aa, w.G2ab,
-                       operand(w, OP_BAA, prec, r), operand(w, OP_BAB, prec, r), s));
-  // C^T[k,l,i,j] = 4/3 sum_rs g_ir g_js G2[k,l,r,s]
-  for (int b = 0; b < 2; ++b) {
-    ModeArgs m1 = mode_base(r, g);  // T1[k,l,r,j] = sum_s g[j,s] G2[k,l,r,s]
-    m1.A = r3; m1.Bn = 1; m1.in1 = b ? w.G2ab : w.G2aa;
-    m1.so1 = r; m1.so0 = 0; m1.sx = 1; m1.sb = 0; m1.out_cols_fast = 0;
-    HIP_TRY(c, launch_mode(GEMM_F64, m1, OperandRef{w.T1, nullptr}, s));
-    ModeArgs m2 = mode_base(r, g);  // C^T[k,l,i,j] = 4/3 sum_r g[i,r] T1[k,l,r,j]
-    m2.A = r2; m2.Bn = r; m2.in1 = w.T1; m2.alpha = 4.0 / 3.0;
-    m2.so1 = r2; m2.so0 = 0; m2.sx = r; m2.sb = 1; m2.out_cols_fast = 1;
-    HIP_TRY(c, launch_mode(GEMM_F64, m2, OperandRef{b ? w.Cab : w.Caa, nullptr}, s));
-  }
-  // ph A operands: L+-[(k,i),(p,s)] = sum_r g[i,r] (X_aa +- X_ab)[k,p,r,s]
-  for (int q : {OP_LP, OP_LM, OP_L3})
-    HIP_TRY(c, launch_zero_kpad(prec, r, ld, operand(w, q, prec, r), s));
-  for (int b = 0; b < 2; ++b) {
-    ModeArgs m = mode_base(r, g);
-    m.A = r2; m.Bn = r; m.in1 = Xaa; m.in2 = Xab; m.c2 = b ? -1.0 : 1.0;
-    m.adiv = r; m.so1 = (int64_t)r * ld; m.so0 = r; m.sx = ld; m.sb = 1; m.out_cols_fast = 1;
-    HIP_TRY(c, launch_mode(prec, m, operand(w, b ? OP_LM : OP_LP, prec, r), s));
-  }
-  {  // L3[(k,j),(p,s)] = sum_r g[j,r] X_ab[k,p,s,r]
-    ModeArgs m = mode_base(r, g);
-    m.A = r3; m.Bn = 1; m.in1 = Xab;
-    m.adiv = r2; m.so1 = (int64_t)r * ld; m.so0 = 1; m.sx = ld; m.sb = 0; m.out_cols_fast = 1;
-    HIP_TRY(c, launch_mode(prec, m, operand(w, OP_L3, prec, r), s));
-  }
-
   // grouped GEMM: 2 pp + 3 ph products
   GemmBatch batch{};
   batch.count = 5;
@@ -211,8 +247,11 @@ acse_status run_map(acse_ctx c, const acse_problem *p, GemmPrec prec, int cfg, c
   set(3, OP_LM, OP_RM, 1.0, w.Pm, r, r3, r2, 1);
   set(4, OP_L3, OP_R3, -2.0, w.E3, r, r2, r3, 1);     // rows (k,j), cols (i,l) -> [i,j,k,l]
   const int use_cfg = cfg >= 0 ? cfg : gemm_default_cfg(prec, (int)r2, (int)r2);
-  HIP_TRY(c, gemm_launch(prec, use_cfg, batch, s));
-
+  {
+    StageTimer t3(c, 3);
+    HIP_TRY(c, gemm_launch(prec, use_cfg, batch, s));
+  }
+  StageTimer t4(c, 4);
   HIP_TRY(c, launch_assemble(r, g, w.t, w.Zaa, w.Zab, w.Pp, w.Pm, w.E3, w.Saa, w.Sab, s));
   HIP_TRY(c, launch_finish(r, sigma, w.Saa, w.Sab, w.Caa, w.Cab, Oaa, Oab, act, Maa, Mab,
                            w.partial, w.scal + slot, s));
@@ -315,10 +354,38 @@ acse_status acse_create(acse_ctx *out, int device, void *hip_stream, int32_t r_m
   return ACSE_OK;
 }
 
+acse_status acse_profile_enable(acse_ctx ctx, int32_t enable) {
+  if (!ctx) return ACSE_ERR_ARG;
+  HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
+  for (auto &q : ctx->recs) { ctx->pool.push_back(q.a); ctx->pool.push_back(q.b); }
+  ctx->recs.clear();
+  for (int s = 0; s < ACSE_NUM_STAGES; ++s) { ctx->ms[s] = 0.0; ctx->count[s] = 0; }
+  ctx->profiling = enable != 0;
+  return ACSE_OK;
+}
+
+acse_status acse_profile_read(acse_ctx ctx, acse_profile_data *out) {
+  if (!ctx || !out) return ACSE_ERR_ARG;
+  HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
+  for (auto &q : ctx->recs) {
+    float ms = 0.0f;
+    HIP_TRY(ctx, hipEventElapsedTime(&ms, q.a, q.b));
+    ctx->ms[q.stage] += ms;
+    ctx->count[q.stage] += 1;
+    ctx->pool.push_back(q.a);
+    ctx->pool.push_back(q.b);
+  }
+  ctx->recs.clear();
+  for (int s = 0; s < ACSE_NUM_STAGES; ++s) { out->ms[s] = ctx->ms[s]; out->count[s] = ctx->count[s]; }
+  return ACSE_OK;
+}
+
 acse_status acse_destroy(acse_ctx ctx) {
   if (!ctx) return ACSE_ERR_ARG;
   (void)hipSetDevice(ctx->device);
   (void)hipStreamSynchronize(ctx->stream);
+  for (auto &q : ctx->recs) { (void)hipEventDestroy(q.a); (void)hipEventDestroy(q.b); }
+  for (auto e : ctx->pool) (void)hipEventDestroy(e);
   (void)hipFree(ctx->base);
   delete ctx;
   return ACSE_OK;
@@ -341,7 +408,10 @@ acse_status acse_residual(acse_ctx ctx, const acse_problem *prob, const acse_opt
   const int cfg = opts ? opts->tile : -1;
   if ((st = prep_rdm_operands(ctx, prob, prec)) != ACSE_OK) return st;
   const int N = prob->n_alpha + prob->n_beta;
-  HIP_TRY(ctx, launch_fold(prob->r, N, prob->h, prob->V, ctx->ws.Aaa, ctx->ws.Aab, ctx->stream));
+  {
+    StageTimer t1(ctx, 1);
+    HIP_TRY(ctx, launch_fold(prob->r, N, prob->h, prob->V, ctx->ws.Aaa, ctx->ws.Aab, ctx->stream));
+  }
   const ActiveBits none{};
   if ((st = run_map(ctx, prob, prec, cfg, ctx->ws.Aaa, ctx->ws.Aab, -1.0, R_aa, R_ab, none, nullptr,
                     nullptr, 0)) != ACSE_OK)
@@ -371,8 +441,11 @@ acse_status acse_energy(acse_ctx ctx, const acse_problem *prob, double *E_host) 
   if (!E_host) return fail(ctx, ACSE_ERR_ARG, "E_host is NULL");
   HIP_TRY(ctx, hipSetDevice(ctx->device));
   const int N = prob->n_alpha + prob->n_beta;
-  HIP_TRY(ctx, launch_energy(prob->r, N, prob->h, prob->V, prob->d2aa, prob->d2ab, ctx->ws.partial,
-                             ctx->ws.scal + 1, ctx->stream));
+  {
+    StageTimer t5(ctx, 5);
+    HIP_TRY(ctx, launch_energy(prob->r, N, prob->h, prob->V, prob->d2aa, prob->d2ab, ctx->ws.partial,
+                               ctx->ws.scal + 1, ctx->stream));
+  }
   return fetch_scalars(ctx, nullptr, E_host);
 }
 
@@ -398,7 +471,10 @@ acse_status acse_step(acse_ctx ctx, acse_problem *prob, double eps, const acse_o
   const ActiveBits act = make_bits(opts, r, &masked);
 
   if ((st = prep_rdm_operands(ctx, prob, prec)) != ACSE_OK) return st;
-  HIP_TRY(ctx, launch_fold(r, N, prob->h, prob->V, w.Aaa, w.Aab, s));
+  {
+    StageTimer t1(ctx, 1);
+    HIP_TRY(ctx, launch_fold(r, N, prob->h, prob->V, w.Aaa, w.Aab, s));
+  }
   // R = F(K), ||R||^2 -> scal[0], masked copy -> M
   if ((st = run_map(ctx, prob, prec, cfg, w.Aaa, w.Aab, -1.0, Raa, Rab, act,
                     masked ? w.Maa : nullptr, masked ? w.Mab : nullptr, 0)) != ACSE_OK)
@@ -408,12 +484,16 @@ acse_status acse_step(acse_ctx ctx, acse_problem *prob, double eps, const acse_o
                     ActiveBits{}, nullptr, nullptr, 2)) != ACSE_OK)
     return st;
   // 2D <- 2D + eps U, trace restoration, 1-RDM contraction, energy (FP64)
-  HIP_TRY(ctx, launch_traces(r, prob->d2aa, prob->d2ab, w.scal + 4, s));
-  HIP_TRY(ctx, launch_axpy2(r, eps, prob->d2aa, prob->d2ab, Uaa, Uab, w.Naa, w.Nab, s));
-  HIP_TRY(ctx, launch_traces(r, w.Naa, w.Nab, w.scal + 6, s));
-  HIP_TRY(ctx, launch_rescale(r, w.scal + 4, w.Naa, w.Nab, prob->d2aa, prob->d2ab, s));
-  HIP_TRY(ctx, launch_contract_1rdm(r, N, prob->d2aa, prob->d2ab, prob->d1, s));
-  HIP_TRY(ctx, launch_energy(r, N, prob->h, prob->V, prob->d2aa, prob->d2ab, w.partial, w.scal + 1, s));
+  {
+    StageTimer t5(ctx, 5);
+    HIP_TRY(ctx, launch_traces(r, prob->d2aa, prob->d2ab, w.scal + 4, s));
+    HIP_TRY(ctx, launch_axpy2(r, eps, prob->d2aa, prob->d2ab, Uaa, Uab, w.Naa, w.Nab, s));
+    HIP_TRY(ctx, launch_traces(r, w.Naa, w.Nab, w.scal + 6, s));
+    HIP_TRY(ctx, launch_rescale(r, w.scal + 4, w.Naa, w.Nab, prob->d2aa, prob->d2ab, s));
+    HIP_TRY(ctx, launch_contract_1rdm(r, N, prob->d2aa, prob->d2ab, prob->d1, s));
+    HIP_TRY(ctx, launch_energy(r, N, prob->h, prob->V, prob->d2aa, prob->d2ab, w.partial,
+                               w.scal + 1, s));
+  }
   return fetch_scalars(ctx, norm2_host, E_host);
 }
 
