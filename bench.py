@@ -101,6 +101,7 @@ def main():
     results = {}
     for mode in args.modes.split(","):
         opts = acse.Context.options(mode)
+        best_tile, tile_ms = ctx.autotune_raw(prob, opts)
         # warmup
         for _ in range(args.warmup):
             restore()
@@ -163,6 +164,7 @@ def main():
             stage_ms_per_step={k: v[0] / args.steps for k, v in prof.items()},
             useful_tflops_step=2 * gemm_flops(r) / (ms * 1e-3) / 1e12,
             error_vs_oracle=err, energy1=E1, norm2=n2,
+            tile_config=best_tile, tile_gemm_ms=tile_ms,
         )
 
     head = args.modes.split(",")[0]

@@ -152,6 +152,15 @@ typedef struct {
 acse_status acse_profile_enable(acse_ctx ctx, int32_t enable);
 acse_status acse_profile_read(acse_ctx ctx, acse_profile_data *out);
 
+/* Autotuner: times one residual map per GEMM tile configuration on this
+ * problem (after a warm-up) and caches the fastest for (r, precision); later
+ * calls with opts->tile = -1 use it.  Writes the chosen configuration index to
+ * *best_tile and, if times_ms is not NULL, the grouped-GEMM time of every
+ * configuration (times_ms[0..n-1], n = ACSE_NUM_TILE_CONFIGS).  Synchronises. */
+#define ACSE_NUM_TILE_CONFIGS 3
+acse_status acse_autotune(acse_ctx ctx, const acse_problem *prob, const acse_options *opts,
+                          int32_t *best_tile, double *times_ms);
+
 /* Human-readable name of a status code (static storage). */
 const char *acse_status_str(acse_status s);
 

@@ -31,7 +31,8 @@ STATUS = {0: "ACSE_OK", 1: "ACSE_ERR_ARG", 2: "ACSE_ERR_SHAPE", 3: "ACSE_ERR_ALI
 # Every function declared in include/acse.h.
 EXPORTS = ("acse_create", "acse_destroy", "acse_set_stream", "acse_residual", "acse_update_map",
            "acse_energy", "acse_step", "acse_status_str", "acse_last_error",
-           "acse_workspace_bytes", "acse_profile_enable", "acse_profile_read")
+           "acse_workspace_bytes", "acse_profile_enable", "acse_profile_read", "acse_autotune")
+NUM_TILE_CONFIGS = 3
 NUM_STAGES = 6
 STAGES = ("rdm_operands", "fold", "transforms", "gemm", "assembly", "step_tail")
 
@@ -67,6 +68,8 @@ _sig = {
     "acse_workspace_bytes": (ctypes.c_int64, [_P]),
     "acse_profile_enable": (ctypes.c_int, [_P, ctypes.c_int32]),
     "acse_profile_read": (ctypes.c_int, [_P, ctypes.POINTER(ProfileData)]),
+    "acse_autotune": (ctypes.c_int, [_P, ctypes.POINTER(Problem), ctypes.POINTER(Options),
+                                     ctypes.POINTER(ctypes.c_int32), _D]),
 }
 for _name, (_res, _args) in _sig.items():
     _fn = getattr(_lib, _name)
@@ -129,6 +132,15 @@ class Context:
         d = ProfileData()
         self._check(_lib.acse_profile_read(self._h, ctypes.byref(d)))
         return {STAGES[i]: (d.ms[i], d.count[i]) for i in range(NUM_STAGES)}
+
+    def autotune_raw(self, prob, opts):
+        """Times every GEMM tile configuration on this problem and caches the best
+        for (r, precision); returns (best index, [ms per configuration])."""
+        best = ctypes.c_int32(-1)
+        times = (ctypes.c_double * NUM_TILE_CONFIGS)()
+        self._check(_lib.acse_autotune(self._h, ctypes.byref(prob), ctypes.byref(opts),
+                                       ctypes.byref(best), times))
+        return best.value, list(times)
 
     def _check(self, st):
         if st != 0:

@@ -19,6 +19,8 @@
 #include <cstdio>
 #include <cstring>
 #include <string>
+#include <map>
+#include <utility>
 #include <vector>
 
 #include "../../include/acse.h"
@@ -57,6 +59,7 @@ struct acse_ctx_s {
   std::vector<hipEvent_t> pool;
   double ms[ACSE_NUM_STAGES] = {};
   int64_t count[ACSE_NUM_STAGES] = {};
+  std::map<std::pair<int, int>, int> tuned;  // (r, precision) -> tile configuration
 };
 
 namespace {
@@ -246,7 +249,11 @@ acse_status run_map(acse_ctx c, const acse_problem *p, GemmPrec prec, int cfg, c
   set(2, OP_LP, OP_RP, 1.0, w.Pp, r, r3, r2, 1);      // rows (k,i), cols (j,l) -> [i,j,k,l]
   set(3, OP_LM, OP_RM, 1.0, w.Pm, r, r3, r2, 1);
   set(4, OP_L3, OP_R3, -2.0, w.E3, r, r2, r3, 1);     // rows (k,j), cols (i,l) -> [i,j,k,l]
-  const int use_cfg = cfg >= 0 ? cfg : gemm_default_cfg(prec, (int)r2, (int)r2);
+  int use_cfg = cfg;
+  if (use_cfg < 0) {
+    auto it = c->tuned.find({r, (int)prec});
+    use_cfg = it != c->tuned.end() ? it->second : gemm_default_cfg(prec, (int)r2, (int)r2);
+  }
   {
     StageTimer t3(c, 3);
     HIP_TRY(c, gemm_launch(prec, use_cfg, batch, s));
@@ -417,6 +424,63 @@ acse_status acse_residual(acse_ctx ctx, const acse_problem *prob, const acse_opt
                     nullptr, 0)) != ACSE_OK)
     return st;
   return fetch_scalars(ctx, norm2_host, nullptr);
+}
+
+acse_status acse_autotune(acse_ctx ctx, const acse_problem *prob, const acse_options *opts,
+                          int32_t *best_tile, double *times_ms) {
+  acse_status st = validate(ctx, prob, opts);
+  if (st != ACSE_OK) return st;
+  if (!best_tile) return fail(ctx, ACSE_ERR_ARG, "best_tile is NULL");
+  HIP_TRY(ctx, hipSetDevice(ctx->device));
+  const GemmPrec prec = prec_of(opts);
+  const int r = prob->r;
+  const int N = prob->n_alpha + prob->n_beta;
+  Workspace &w = ctx->ws;
+  if ((st = prep_rdm_operands(ctx, prob, prec)) != ACSE_OK) return st;
+  HIP_TRY(ctx, launch_fold(r, N, prob->h, prob->V, w.Aaa, w.Aab, ctx->stream));
+  // time the grouped GEMM of one residual map per configuration (profiling
+  // state of the caller is saved and restored)
+  const bool was = ctx->profiling;
+  auto saved = std::move(ctx->recs);
+  ctx->recs.clear();
+  double best = 1e300;
+  int arg = 0;
+  const ActiveBits none{};
+  for (int cfg = 0; cfg < ACSE_NUM_TILE_CONFIGS; ++cfg) {
+    ctx->profiling = false;
+    if ((st = run_map(ctx, prob, prec, cfg, w.Aaa, w.Aab, -1.0, w.Raa, w.Rab, none, nullptr, nullptr,
+                      0)) != ACSE_OK)
+      break;
+    ctx->profiling = true;
+    for (int rep = 0; rep < 2; ++rep)
+      if ((st = run_map(ctx, prob, prec, cfg, w.Aaa, w.Aab, -1.0, w.Raa, w.Rab, none, nullptr,
+                        nullptr, 0)) != ACSE_OK)
+        break;
+    if (st != ACSE_OK) break;
+    if (hipStreamSynchronize(ctx->stream) != hipSuccess) { st = fail(ctx, ACSE_ERR_HIP, "sync"); break; }
+    double ms = 0.0;
+    int n = 0;
+    for (auto &q : ctx->recs) {
+      if (q.stage == 3) {
+        float e = 0.0f;
+        (void)hipEventElapsedTime(&e, q.a, q.b);
+        ms += e;
+        ++n;
+      }
+      ctx->pool.push_back(q.a);
+      ctx->pool.push_back(q.b);
+    }
+    ctx->recs.clear();
+    ms = n ? ms / n : 1e300;
+    if (times_ms) times_ms[cfg] = ms;
+    if (ms < best) { best = ms; arg = cfg; }
+  }
+  ctx->profiling = was;
+  ctx->recs = std::move(saved);
+  if (st != ACSE_OK) return st;
+  ctx->tuned[{r, (int)prec}] = arg;
+  *best_tile = arg;
+  return ACSE_OK;
 }
 
 acse_status acse_update_map(acse_ctx ctx, const acse_problem *prob, const acse_options *opts,

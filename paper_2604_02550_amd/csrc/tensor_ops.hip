@@ -7,6 +7,8 @@
 // GEMM operands are [rows][ld] matrices (rows = pair index, ld >= padded K)
 // in the contraction precision; the F64/F32/BF16x3 variants are selected by
 // the OpT template parameter (BF16x3 writes a hi and a lo plane).
+#include <algorithm>
+
 #include "tensor_ops.h"
 
 namespace acse {
@@ -33,6 +35,13 @@ struct OutBF16x3 {
 };
 
 __device__ inline int64_t gtid() { return (int64_t)blockIdx.x * blockDim.x + threadIdx.x; }
+
+// Unconditional load from a clamped, always valid address: staging loops issue
+// a whole batch of these before consuming any, so the loads overlap (a guarded
+// load would make the compiler wait for each one before the next).
+__device__ inline double ld_ok(const double *__restrict__ p, int64_t off, bool ok) {
+  return p[ok ? off : 0];
+}
 
 // ---------------------------------------------------------------------------
 // Fold of Eq. (2): X_A blocks of the reduced Hamiltonian
@@ -147,6 +156,7 @@ __global__ void k_f_partial(int r, const double *__restrict__ Aaa, const double 
   const int s = e % r, p = (e / r) % r, k = e / ((int64_t)r * r);
   const int64_t base = (int64_t)k * r3 + (int64_t)p * r * r;
   double acc = 0.0;
+#pragma unroll 8
   for (int rr = 0; rr < r; ++rr)
     acc += (Aaa[base + (int64_t)rr * r + s] - Aab[base + (int64_t)s * r + rr]) * g[p * r + rr];
   part[e] = acc;  // [k][p][s]
@@ -164,53 +174,174 @@ __global__ void k_f_reduce(int r, const double *__restrict__ part, double *__res
 // Mode product:  out[a, x, b] = alpha * sum_y M(x, y) * (c1 in1 + c2 in2)[a, y, b]
 // in* contiguous [A][r][Bn]; M(x,y) = g[x*r+y] or g[y*r+x] (transposed);
 // output element address (a/adiv)*so1 + (a%adiv)*so0 + x*sx + b*sb.
-// A block owns NCOL consecutive (a,b) columns; the r x NCOL input panel and
-// M are staged in LDS so every input element is read from HBM once.
+// A block owns kModeCols consecutive (a,b) columns.  The r x kModeCols input
+// panel and M^T are staged in LDS (every input element is read once); each
+// thread accumulates a 4 (x) x 4 (column) register tile; the result panel is
+// staged back through LDS and written with lanes along whichever of x or the
+// columns is contiguous in the output.
 // ---------------------------------------------------------------------------
 constexpr int kModeCols = 64;
+constexpr int kStage = 8;  // global loads in flight per thread in LDS staging loops
 
 template <class O>
 __global__ void __launch_bounds__(256)
 k_mode(ModeArgs m, O out) {
   extern __shared__ double mode_smem[];
   const int r = m.r;
-  const int ldm = r + 1;
-  double *Ms = mode_smem;              // [r][r+1]
-  double *T = mode_smem + r * ldm;     // [r][kModeCols]
-  const int64_t ncols = (int64_t)m.A * m.Bn;
-  const int64_t c0 = (int64_t)blockIdx.x * kModeCols;
-  const int nc = (int)min<int64_t>(kModeCols, ncols - c0);
-  for (int e = threadIdx.x; e < r * r; e += 256) {
-    const int x = e / r, y = e % r;
-    Ms[x * ldm + y] = m.transpose_m ? m.g[y * r + x] : m.g[x * r + y];
-  }
-  const bool along_b = m.Bn >= kModeCols;
-  for (int e = threadIdx.x; e < r * kModeCols; e += 256) {
-    int y, c;
-    if (along_b) { y = e / kModeCols; c = e % kModeCols; } else { c = e / r; y = e % r; }
-    double v = 0.0;
-    if (c < nc) {
-      const int64_t col = c0 + c;
-      const int64_t a = col / m.Bn, b = col % m.Bn;
-      const int64_t off = (a * r + y) * m.Bn + b;
-      v = m.c1 * m.in1[off];
-      if (m.in2) v += m.c2 * m.in2[off];
+  const int rp = (r + 3) & ~3;
+  double *Mt = mode_smem;                 // [y][x], x padded to rp
+  double *T = mode_smem + r * rp;         // [y][c]; reused as the output panel [x][c]
+  // column indices fit in 32 bits (A * Bn <= r^4)
+  const int Bn = (int)m.Bn;
+  const int ncols = (int)(m.A * m.Bn);
+  const int c0 = blockIdx.x * kModeCols;
+  const int nc = min(kModeCols, ncols - c0);
+  const int tid = threadIdx.x;
+  // a missing second input reads the first one with weight zero
+  const double *in2 = m.in2 ? m.in2 : m.in1;
+  const double c1 = m.c1, c2 = m.in2 ? m.c2 : 0.0;
+
+  // --- M^T into LDS: flat walk over (y, x) without divisions per element
+  {
+    int y = tid / rp, x = tid - (tid / rp) * rp;
+    const int dy = 256 / rp, dx = 256 - dy * rp;
+    for (int base = 0; base < r * rp; base += 256 * kStage) {
+      double v[kStage];
+      bool ok[kStage];
+      int yy[kStage], xx[kStage];
+#pragma unroll
+      for (int u = 0; u < kStage; ++u) {
+        yy[u] = y; xx[u] = x;
+        ok[u] = y < r && x < r;
+        v[u] = ld_ok(m.g, m.transpose_m ? y * r + x : x * r + y, ok[u]);
+        y += dy; x += dx;
+        if (x >= rp) { x -= rp; ++y; }
+      }
+#pragma unroll
+      for (int u = 0; u < kStage; ++u)
+        if (yy[u] < r) Mt[yy[u] * rp + xx[u]] = ok[u] ? v[u] : 0.0;
     }
-    T[y * kModeCols + c] = v;
+  }
+  // --- input panel T[y][c] = (c1 in1 + c2 in2)[a, y, b] for column c0 + c = a*Bn + b
+  if (Bn == 1) {
+    // the panel is one contiguous run in[c0*r + f], f = c*r + y
+    const int64_t base_off = (int64_t)c0 * r;
+    const int tot = nc * r;
+    int c = tid / r, y = tid - (tid / r) * r;
+    const int dc = 256 / r, dy = 256 - dc * r;
+    for (int f0 = 0; f0 < r * kModeCols; f0 += 256 * kStage) {
+      double v1[kStage], v2[kStage];
+      int cc[kStage], yy[kStage];
+      bool ok[kStage];
+#pragma unroll
+      for (int u = 0; u < kStage; ++u) {
+        const int f = f0 + u * 256 + tid;
+        cc[u] = c; yy[u] = y;
+        ok[u] = f < tot;
+        v1[u] = ld_ok(m.in1, base_off + f, ok[u]);
+        v2[u] = ld_ok(in2, base_off + f, ok[u]);
+        y += dy; c += dc;
+        if (y >= r) { y -= r; ++c; }
+      }
+#pragma unroll
+      for (int u = 0; u < kStage; ++u)
+        if (cc[u] < kModeCols) T[yy[u] * kModeCols + cc[u]] = ok[u] ? c1 * v1[u] + c2 * v2[u] : 0.0;
+    }
+  } else {
+    // each thread owns one column (lanes along consecutive b), rows y step by 4
+    const int c = tid & (kModeCols - 1);
+    const bool okc = c < nc;
+    const int col = c0 + (okc ? c : 0);
+    const int a = col / Bn, b = col - a * Bn;
+    const int64_t off0 = ((int64_t)a * r) * Bn + b;
+    const int ystep = 256 / kModeCols;
+    for (int y0 = tid / kModeCols; y0 < r; y0 += ystep * kStage) {
+      double v1[kStage], v2[kStage];
+#pragma unroll
+      for (int u = 0; u < kStage; ++u) {
+        const int y = y0 + u * ystep;
+        const bool ok = okc && y < r;
+        const int64_t off = off0 + (int64_t)y * Bn;
+        v1[u] = ld_ok(m.in1, off, ok);
+        v2[u] = ld_ok(in2, off, ok);
+      }
+#pragma unroll
+      for (int u = 0; u < kStage; ++u) {
+        const int y = y0 + u * ystep;
+        if (y < r) T[y * kModeCols + c] = okc ? c1 * v1[u] + c2 * v2[u] : 0.0;
+      }
+    }
   }
   __syncthreads();
-  // lanes run along the columns when the output is contiguous in the column
-  // index, else along x
-  for (int e = threadIdx.x; e < r * kModeCols; e += 256) {
-    int x, c;
-    if (m.out_cols_fast) { x = e / kModeCols; c = e % kModeCols; } else { c = e / r; x = e % r; }
-    if (c >= nc) continue;
-    double acc = 0.0;
-    for (int y = 0; y < r; ++y) acc += Ms[x * ldm + y] * T[y * kModeCols + c];
-    const int64_t col = c0 + c;
-    const int64_t a = col / m.Bn, b = col % m.Bn;
-    const int64_t off = (a / m.adiv) * m.so1 + (a % m.adiv) * m.so0 + (int64_t)x * m.sx + b * m.sb;
-    out.put(off, m.alpha * acc);
+  // --- 4 x 4 register tiles: rows x = xg..xg+3, columns cg..cg+3
+  const int cg = (tid & 15) * 4;
+  const int xg0 = (tid >> 4) * 4;
+  double acc[2][4][4];
+#pragma unroll
+  for (int u = 0; u < 2; ++u)
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+      for (int j = 0; j < 4; ++j) acc[u][i][j] = 0.0;
+#pragma unroll
+  for (int u = 0; u < 2; ++u) {
+    const int xg = xg0 + u * 64;
+    if (xg >= r) break;
+    const double *mp = Mt + xg;
+    const double *tp = T + cg;
+    for (int y = 0; y < r; ++y) {
+      double mv[4], tv[4];
+#pragma unroll
+      for (int i = 0; i < 4; ++i) mv[i] = mp[i];
+#pragma unroll
+      for (int j = 0; j < 4; ++j) tv[j] = tp[j];
+      mp += rp;
+      tp += kModeCols;
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) acc[u][i][j] += mv[i] * tv[j];
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int u = 0; u < 2; ++u) {
+    const int xg = xg0 + u * 64;
+    if (xg >= r) break;
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+      if (xg + i < r)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) T[(xg + i) * kModeCols + cg + j] = acc[u][i][j];
+  }
+  __syncthreads();
+  // --- store: lanes along columns (output contiguous in (a,b)) or along x
+  const double alpha = m.alpha;
+  if (m.out_cols_fast) {
+    const int c = tid & (kModeCols - 1);
+    if (c < nc) {
+      const int col = c0 + c;
+      const int a = col / Bn, b = col - a * Bn;
+      const int adiv = (int)m.adiv;
+      const int a1 = a / adiv, a0 = a - a1 * adiv;
+      const int64_t off0 = (int64_t)a1 * m.so1 + (int64_t)a0 * m.so0 + (int64_t)b * m.sb;
+      for (int x = tid / kModeCols; x < r; x += 256 / kModeCols)
+        out.put(off0 + (int64_t)x * m.sx, alpha * T[x * kModeCols + c]);
+    }
+  } else {
+    // x fastest: flat walk over (c, x)
+    int c = tid / r, x = tid - (tid / r) * r;
+    const int dc = 256 / r, dx = 256 - dc * r;
+    const int adiv = (int)m.adiv;
+    for (int f = tid; f < nc * r; f += 256) {
+      const int col = c0 + c;
+      const int a = col / Bn, b = col - a * Bn;
+      const int a1 = a / adiv, a0 = a - a1 * adiv;
+      const int64_t off = (int64_t)a1 * m.so1 + (int64_t)a0 * m.so0 + (int64_t)x * m.sx + (int64_t)b * m.sb;
+      out.put(off, alpha * T[x * kModeCols + c]);
+      x += dx; c += dc;
+      if (x >= r) { x -= r; ++c; }
+    }
   }
 }
 
@@ -255,68 +386,142 @@ __global__ void k_g2(int r, int ld, const double *__restrict__ Aaa, const double
 //   S_ab = Z_ab + g_jl t_ik + g_ik t_jl
 //               - (E2[i,j,k,l] + E2[j,i,l,k] - E3[i,j,k,l] - E3[j,i,l,k])
 // with E1 = P+ + P-, E2 = P+ - P- (all stored [i,j,k,l]).
+// One block per unordered pair {i <= j} writes the slabs S[i,j,:,:] and
+// S[j,i,:,:]; for a chunk of kKC values of k it stages, for both slabs (i,j)
+// and (j,i) of P+, P- and E3, the rows X[.,.,k,:] and the column stripes
+// X[.,.,:,k] in LDS, so every global read is a contiguous run.
 // ---------------------------------------------------------------------------
-__global__ void k_assemble(int r, const double *__restrict__ g, const double *__restrict__ t,
-                           const double *__restrict__ Zaa, const double *__restrict__ Zab,
-                           const double *__restrict__ Pp, const double *__restrict__ Pm,
-                           const double *__restrict__ E3, double *__restrict__ Saa,
-                           double *__restrict__ Sab) {
+constexpr int kKC = 8;
+
+__global__ void __launch_bounds__(256)
+k_assemble(int r, const double *__restrict__ g, const double *__restrict__ t,
+           const double *__restrict__ Zaa, const double *__restrict__ Zab,
+           const double *__restrict__ Pp, const double *__restrict__ Pm,
+           const double *__restrict__ E3, double *__restrict__ Saa, double *__restrict__ Sab) {
+  extern __shared__ double asm_smem[];
+  // pair index -> (i, j), i <= j
+  int i = 0, rem = blockIdx.x;
+  while (rem >= r - i) { rem -= r - i; ++i; }
+  const int j = i + rem;
   const int64_t r2 = (int64_t)r * r;
-  const int64_t n4 = r2 * r2;
-  const int64_t e = gtid();
-  if (e >= n4) return;
-  const int l = e % r, k = (e / r) % r, j = (e / r2) % r, i = e / (r2 * r);
-  const int64_t ijkl = e;
-  const int64_t jikl = ((int64_t)j * r + i) * r2 + (int64_t)k * r + l;
-  const int64_t ijlk = ((int64_t)i * r + j) * r2 + (int64_t)l * r + k;
-  const int64_t jilk = ((int64_t)j * r + i) * r2 + (int64_t)l * r + k;
-  const double pp_ijkl = Pp[ijkl], pm_ijkl = Pm[ijkl];
-  const double pp_jilk = Pp[jilk], pm_jilk = Pm[jilk];
-  const double e1 = (pp_ijkl + pm_ijkl) - (Pp[jikl] + Pm[jikl]) - (Pp[ijlk] + Pm[ijlk]) + (pp_jilk + pm_jilk);
-  const double e2 = (pp_ijkl - pm_ijkl) + (pp_jilk - pm_jilk) - E3[ijkl] - E3[jilk];
-  const double gt_aa = g[i * r + l] * t[j * r + k] - g[j * r + l] * t[i * r + k] -
-                       g[i * r + k] * t[j * r + l] + g[j * r + k] * t[i * r + l];
-  const double gt_ab = g[j * r + l] * t[i * r + k] + g[i * r + k] * t[j * r + l];
-  Saa[e] = Zaa[e] - gt_aa - e1;
-  Sab[e] = Zab[e] + gt_ab - e2;
+  const double *X[3] = {Pp, Pm, E3};
+  const int64_t slab[2] = {((int64_t)i * r + j) * r2, ((int64_t)j * r + i) * r2};
+  // rowp[s][x][kk][l] and colp[s][x][l][kk] (padded)
+  const int RW = kKC * r, CW = r * (kKC + 1);
+  double *rowp = asm_smem;
+  double *colp = asm_smem + 6 * RW;
+  const int nslab = (i == j) ? 1 : 2;
+  for (int k0 = 0; k0 < r; k0 += kKC) {
+    const int kc = min(kKC, r - k0);
+    const int tot = 6 * kc * r;
+    for (int base = 0; base < tot; base += 256 * kStage) {
+      double vr[kStage], vc[kStage];
+      int dr[kStage], dc[kStage];
+#pragma unroll
+      for (int u = 0; u < kStage; ++u) {
+        const int e = base + u * 256 + threadIdx.x;
+        const int sx = e / (kc * r), w = e - sx * (kc * r);
+        const int s = sx / 3, x = sx - 3 * s;
+        const int kk = w / r, l = w - kk * r;      // row stripe X[s][k0+kk][l]
+        const int l2 = w / kc, kk2 = w - l2 * kc;  // column stripe X[s][l2][k0+kk2]
+        dr[u] = sx * RW + kk * r + l;
+        dc[u] = sx * CW + l2 * (kKC + 1) + kk2;
+        const bool ok = e < tot;
+        const double *Xp = X[ok ? x : 0];
+        vr[u] = ld_ok(Xp, slab[ok ? s : 0] + (int64_t)(k0 + kk) * r + l, ok);
+        vc[u] = ld_ok(Xp, slab[ok ? s : 0] + (int64_t)l2 * r + k0 + kk2, ok);
+      }
+#pragma unroll
+      for (int u = 0; u < kStage; ++u) {
+        const int e = base + u * 256 + threadIdx.x;
+        if (e < tot) { rowp[dr[u]] = vr[u]; colp[dc[u]] = vc[u]; }
+      }
+    }
+    __syncthreads();
+    for (int e = threadIdx.x; e < nslab * kc * r; e += 256) {
+      const int s = e / (kc * r), w = e % (kc * r);
+      const int kk = w / r, l = w % r;
+      const int k = k0 + kk;
+      const int a = s ? j : i, b = s ? i : j;   // output slab (a, b)
+      const int o = 1 - s;                      // the other slab (b, a)
+      auto R = [&](int sl, int x) { return rowp[(sl * 3 + x) * RW + kk * r + l]; };       // X[sl][k][l]
+      auto Cq = [&](int sl, int x) { return colp[(sl * 3 + x) * CW + l * (kKC + 1) + kk]; };  // X[sl][l][k]
+      const double e1 = (R(s, 0) + R(s, 1)) - (R(o, 0) + R(o, 1)) - (Cq(s, 0) + Cq(s, 1)) +
+                        (Cq(o, 0) + Cq(o, 1));
+      const double e2 = (R(s, 0) - R(s, 1)) + (Cq(o, 0) - Cq(o, 1)) - R(s, 2) - Cq(o, 2);
+      const double gt_aa = g[a * r + l] * t[b * r + k] - g[b * r + l] * t[a * r + k] -
+                           g[a * r + k] * t[b * r + l] + g[b * r + k] * t[a * r + l];
+      const double gt_ab = g[b * r + l] * t[a * r + k] + g[a * r + k] * t[b * r + l];
+      const int64_t out = slab[s] + (int64_t)k * r + l;
+      Saa[out] = Zaa[out] - gt_aa - e1;
+      Sab[out] = Zab[out] + gt_ab - e2;
+    }
+    __syncthreads();
+  }
 }
 
-// Out = S + sigma S^T ((ij)<->(kl)) with S = S' + C^T; optional masked copy; per-block partial
-// sums of 2 Out_aa^2 + 4 Out_ab^2 (deterministic two-pass reduction).
+// Out = S + sigma S^T ((ij)<->(kl)) with S = S' + C^T (C stored [k,l,i,j]),
+// on 32 x 32 tiles of the r^2 x r^2 pair matrix: the (row, col) tile and the
+// mirrored (col, row) tile of S' and C are both read row-wise into LDS.
+// Optional masked copy; per-block partial sums of 2 Out_aa^2 + 4 Out_ab^2.
+constexpr int kFT = 32;
+
 __global__ void __launch_bounds__(256)
 k_finish(int r, double sigma, const double *__restrict__ Saa, const double *__restrict__ Sab,
          const double *__restrict__ Caa, const double *__restrict__ Cab,
          double *__restrict__ Oaa, double *__restrict__ Oab, ActiveBits active,
          double *__restrict__ Maa, double *__restrict__ Mab, double *__restrict__ partial) {
+  __shared__ double sA[kFT][kFT + 1], cA[kFT][kFT + 1], sB[kFT][kFT + 1], cB[kFT][kFT + 1];
   __shared__ double red[256];
   const int64_t r2 = (int64_t)r * r;
-  const int64_t n4 = r2 * r2;
-  const int64_t e = gtid();
+  const int64_t R0 = (int64_t)blockIdx.y * kFT, C0 = (int64_t)blockIdx.x * kFT;
+  const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;  // 32 x 8
   double acc = 0.0;
-  if (e < n4) {
-    const int64_t row = e / r2, col = e % r2;
-    const int64_t tr = col * r2 + row;
-    // S = S' + C^T where C (stored [k,l,i,j]) is the separable gamma-gamma term
-    const double a = (Saa[e] + Caa[tr]) + sigma * (Saa[tr] + Caa[e]);
-    const double b = (Sab[e] + Cab[tr]) + sigma * (Sab[tr] + Cab[e]);
-    Oaa[e] = a;
-    Oab[e] = b;
-    acc = 2.0 * a * a + 4.0 * b * b;
-    if (Maa) {
-      const int l = e % r, k = (e / r) % r, j = (e / r2) % r, i = e / (r2 * r);
-      auto act = [&](int q) { return (active.w[q >> 6] >> (q & 63)) & 1ull; };
-      const bool all_active = act(i) && act(j) && act(k) && act(l);
-      Maa[e] = all_active ? 0.0 : a;
-      Mab[e] = all_active ? 0.0 : b;
+  for (int blk = 0; blk < 2; ++blk) {
+    const double *S = blk ? Sab : Saa;
+    const double *C = blk ? Cab : Caa;
+    double *O = blk ? Oab : Oaa;
+    double *M = blk ? Mab : Maa;
+    const double w = blk ? 4.0 : 2.0;
+#pragma unroll
+    for (int q = 0; q < kFT; q += 8) {
+      const int y = ty + q;
+      const int64_t ra = R0 + y, ca = C0 + tx;   // (row, col) tile
+      const int64_t rb = C0 + y, cb = R0 + tx;   // mirrored tile
+      const bool oka = ra < r2 && ca < r2, okb = rb < r2 && cb < r2;
+      const double s1 = ld_ok(S, ra * r2 + ca, oka), c1 = ld_ok(C, ra * r2 + ca, oka);
+      const double s2 = ld_ok(S, rb * r2 + cb, okb), c2 = ld_ok(C, rb * r2 + cb, okb);
+      sA[y][tx] = oka ? s1 : 0.0;
+      cA[y][tx] = oka ? c1 : 0.0;
+      sB[y][tx] = okb ? s2 : 0.0;
+      cB[y][tx] = okb ? c2 : 0.0;
     }
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < kFT; q += 8) {
+      const int y = ty + q;
+      const int64_t row = R0 + y, col = C0 + tx;
+      if (row < r2 && col < r2) {
+        const double v = (sA[y][tx] + cB[tx][y]) + sigma * (sB[tx][y] + cA[y][tx]);
+        const int64_t e = row * r2 + col;
+        O[e] = v;
+        acc += w * v * v;
+        if (M) {
+          const int i = (int)(row / r), j = (int)(row % r), k = (int)(col / r), l = (int)(col % r);
+          auto act = [&](int q2) { return (active.w[q2 >> 6] >> (q2 & 63)) & 1ull; };
+          M[e] = (act(i) && act(j) && act(k) && act(l)) ? 0.0 : v;
+        }
+      }
+    }
+    __syncthreads();
   }
   red[threadIdx.x] = acc;
   __syncthreads();
-  for (int w = 128; w > 0; w >>= 1) {
-    if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+  for (int wv = 128; wv > 0; wv >>= 1) {
+    if (threadIdx.x < wv) red[threadIdx.x] += red[threadIdx.x + wv];
     __syncthreads();
   }
-  if (threadIdx.x == 0) partial[blockIdx.x] = red[0];
+  if (threadIdx.x == 0) partial[blockIdx.y * gridDim.x + blockIdx.x] = red[0];
 }
 
 // Sum of n partials in a fixed order by one block; writes out[0].
@@ -341,15 +546,16 @@ k_reduce_sum(int64_t n, const double *__restrict__ part, double *__restrict__ ou
 // thread reads its 4 j's and 4 k's as consecutive doubles.
 // ---------------------------------------------------------------------------
 constexpr int kTChunk = 32;
-constexpr int kTBlocks = 256;
+constexpr int kTBlocks = 512;
 
 __global__ void __launch_bounds__(256)
 k_t_partial(int r, const double *__restrict__ Waa, const double *__restrict__ Aaa,
             const double *__restrict__ Wab, const double *__restrict__ Aab,
             double *__restrict__ part) {
   extern __shared__ double t_smem[];
-  const int rp = (r + 3) & ~3;
-  double *sWa = t_smem, *sAa = sWa + kTChunk * rp, *sWb = sAa + kTChunk * rp, *sAb = sWb + kTChunk * rp;
+  const int rp = (r + 3) & ~3;      // j / k extent covered by 4 x 4 tiles
+  const int ls = rp + 2;            // LDS row stride (= 2 mod 4 doubles: staging stores spread over banks)
+  double *sWa = t_smem, *sAa = sWa + kTChunk * ls, *sWb = sAa + kTChunk * ls, *sAb = sWb + kTChunk * ls;
   const int64_t X = (int64_t)r * r * r;
   const int64_t per = (X + gridDim.x - 1) / gridDim.x;
   const int64_t x0 = (int64_t)blockIdx.x * per, x1 = min(X, x0 + per);
@@ -360,15 +566,31 @@ k_t_partial(int r, const double *__restrict__ Waa, const double *__restrict__ Aa
 #pragma unroll
     for (int q = 0; q < 16; ++q) acc[u][q] = 0.0;
   for (int64_t xc = x0; xc < x1; xc += kTChunk) {
-    for (int e = threadIdx.x; e < kTChunk * rp; e += 256) {
-      const int c = e % kTChunk, j = e / kTChunk;
-      const int64_t x = xc + c;
-      const bool ok = (j < r) && (x < x1);
-      const int64_t o = (int64_t)j * X + x;
-      sWa[c * rp + j] = ok ? Waa[o] : 0.0;
-      sAa[c * rp + j] = ok ? Aaa[o] : 0.0;
-      sWb[c * rp + j] = ok ? Wab[o] : 0.0;
-      sAb[c * rp + j] = ok ? Aab[o] : 0.0;
+    for (int base = 0; base < kTChunk * rp; base += 256 * 4) {
+      double v[4][4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int e = base + u * 256 + threadIdx.x;
+        const int c = e % kTChunk, j = e / kTChunk;
+        const int64_t x = xc + c;
+        const bool ok = e < kTChunk * rp && (j < r) && (x < x1);
+        const int64_t o = (int64_t)j * X + x;
+        v[u][0] = ld_ok(Waa, o, ok);
+        v[u][1] = ld_ok(Aaa, o, ok);
+        v[u][2] = ld_ok(Wab, o, ok);
+        v[u][3] = ld_ok(Aab, o, ok);
+        if (!ok) v[u][0] = v[u][1] = v[u][2] = v[u][3] = 0.0;
+      }
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int e = base + u * 256 + threadIdx.x;
+        if (e >= kTChunk * rp) continue;
+        const int c = e % kTChunk, j = e / kTChunk;
+        sWa[c * ls + j] = v[u][0];
+        sAa[c * ls + j] = v[u][1];
+        sWb[c * ls + j] = v[u][2];
+        sAb[c * ls + j] = v[u][3];
+      }
     }
     __syncthreads();
 #pragma unroll
@@ -380,8 +602,8 @@ k_t_partial(int r, const double *__restrict__ Waa, const double *__restrict__ Aa
         double wa[4], aa[4], wb[4], ab[4];
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
-          wa[v] = sWa[c * rp + jb + v]; aa[v] = sAa[c * rp + kb + v];
-          wb[v] = sWb[c * rp + jb + v]; ab[v] = sAb[c * rp + kb + v];
+          wa[v] = sWa[c * ls + jb + v]; aa[v] = sAa[c * ls + kb + v];
+          wb[v] = sWb[c * ls + jb + v]; ab[v] = sAb[c * ls + kb + v];
         }
 #pragma unroll
         for (int a = 0; a < 4; ++a)
@@ -405,14 +627,17 @@ k_t_partial(int r, const double *__restrict__ Waa, const double *__restrict__ Aa
   }
 }
 
-// t[j,k] = sum over the per-block partials of k_t_partial.
-__global__ void k_t_reduce(int r, int nsplit_total, const double *__restrict__ part,
-                           double *__restrict__ t) {
-  const int e = (int)gtid();
+// t[j,k] = sum over the per-block partials of k_t_partial: one wavefront per
+// output, lanes stride over the partials, then a shuffle reduction (fixed order).
+__global__ void __launch_bounds__(256)
+k_t_reduce(int r, int nparts, const double *__restrict__ part, double *__restrict__ t) {
+  const int lane = threadIdx.x & 63;
+  const int e = blockIdx.x * 4 + (threadIdx.x >> 6);
   if (e >= r * r) return;
   double acc = 0.0;
-  for (int q = 0; q < nsplit_total; ++q) acc += part[(int64_t)q * r * r + e];
-  t[e] = acc;
+  for (int q = lane; q < nparts; q += 64) acc += part[(int64_t)q * r * r + e];
+  for (int off = 32; off > 0; off >>= 1) acc += __shfl_down(acc, off, 64);
+  if (lane == 0) t[e] = acc;
 }
 
 // ---------------------------------------------------------------------------
@@ -575,7 +800,7 @@ hipError_t launch_f(int r, const double *Aaa, const double *Aab, const double *g
   return hipGetLastError();
 }
 
-size_t mode_lds_bytes(int r) { return (size_t)(r * (r + 1) + r * kModeCols) * sizeof(double); }
+size_t mode_lds_bytes(int r) { return (size_t)(r * ((r + 3) & ~3) + r * kModeCols) * sizeof(double); }
 
 hipError_t launch_mode(GemmPrec prec, const ModeArgs &m, const OperandRef &out, hipStream_t s) {
   if (m.r > kModeMaxR) return hipErrorInvalidValue;
@@ -603,8 +828,13 @@ hipError_t launch_g2(GemmPrec prec, int r, int ld, const double *Aaa, const doub
 hipError_t launch_assemble(int r, const double *g, const double *t, const double *Zaa,
                            const double *Zab, const double *Pp, const double *Pm, const double *E3,
                            double *Saa, double *Sab, hipStream_t s) {
-  const int64_t n4 = (int64_t)r * r * r * r;
-  hipLaunchKernelGGL(k_assemble, grid_for(n4), dim3(256), 0, s, r, g, t, Zaa, Zab, Pp, Pm, E3, Saa, Sab);
+  const size_t lds = (size_t)6 * (kKC * r + r * (kKC + 1)) * sizeof(double);
+  hipError_t err = hipFuncSetAttribute(reinterpret_cast<const void *>(&k_assemble),
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  if (err != hipSuccess) return err;
+  const unsigned npairs = (unsigned)(r * (r + 1) / 2);
+  hipLaunchKernelGGL(k_assemble, dim3(npairs), dim3(256), lds, s, r, g, t, Zaa, Zab, Pp, Pm, E3, Saa,
+                     Sab);
   return hipGetLastError();
 }
 
@@ -612,18 +842,21 @@ hipError_t launch_finish(int r, double sigma, const double *Saa, const double *S
                          const double *Caa, const double *Cab, double *Oaa, double *Oab,
                          const ActiveBits &active, double *Maa, double *Mab, double *partial,
                          double *sum_out, hipStream_t s) {
-  const int64_t n4 = (int64_t)r * r * r * r;
-  const int64_t nb = (n4 + 255) / 256;
-  hipLaunchKernelGGL(k_finish, dim3((unsigned)nb), dim3(256), 0, s, r, sigma, Saa, Sab, Caa, Cab,
-                     Oaa, Oab, active, Maa, Mab, partial);
+  const int64_t nt = ((int64_t)r * r + kFT - 1) / kFT;
+  const int64_t nb = nt * nt;
+  hipLaunchKernelGGL(k_finish, dim3((unsigned)nt, (unsigned)nt), dim3(256), 0, s, r, sigma, Saa, Sab,
+                     Caa, Cab, Oaa, Oab, active, Maa, Mab, partial);
   hipLaunchKernelGGL(k_reduce_sum, dim3(1), dim3(256), 0, s, nb, partial, sum_out);
   return hipGetLastError();
 }
 
-int64_t finish_partials(int r) { return ((int64_t)r * r * r * r + 255) / 256; }
+int64_t finish_partials(int r) {
+  const int64_t nt = ((int64_t)r * r + kFT - 1) / kFT;
+  return std::max<int64_t>(nt * nt, ((int64_t)r * r * r * r + 255) / 256);
+}
 
 hipError_t launch_t_reduce(int r, int nparts, const double *part, double *t, hipStream_t s) {
-  hipLaunchKernelGGL(k_t_reduce, grid_for((int64_t)r * r), dim3(256), 0, s, r, nparts, part, t);
+  hipLaunchKernelGGL(k_t_reduce, dim3((unsigned)((r * r + 3) / 4)), dim3(256), 0, s, r, nparts, part, t);
   return hipGetLastError();
 }
 
@@ -631,8 +864,8 @@ int t_partial_blocks() { return kTBlocks; }
 
 hipError_t launch_t(int r, const double *Waa, const double *Aaa, const double *Wab,
                     const double *Aab, double *part, double *t, hipStream_t s) {
-  const int rp = (r + 3) & ~3;
-  const size_t lds = (size_t)4 * kTChunk * rp * sizeof(double);
+  const int ls = ((r + 3) & ~3) + 2;
+  const size_t lds = (size_t)4 * kTChunk * ls * sizeof(double);
   hipError_t err = hipFuncSetAttribute(reinterpret_cast<const void *>(&k_t_partial),
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   if (err != hipSuccess) return err;

@@ -119,6 +119,16 @@ def test_every_tile_config(ctx, tile):
     assert rel(cpu(Raa), raa) < TOL64 and rel(cpu(Rab), rab) < TOL64
 
 
+def test_autotune_then_parity(ctx, acse):
+    p = PROBLEMS["r13"]()
+    prob, keep = ctx.problem(p["h"], p["V"], p["gamma"], p["d2aa"], p["d2ab"], p["N"] // 2)
+    best, times = ctx.autotune_raw(prob, ctx.options("fp64"))
+    assert 0 <= best < acse.NUM_TILE_CONFIGS and all(t > 0 for t in times)
+    raa, rab, n2 = ost.residual(p["h"], p["V"], p["N"], p["gamma"], p["d2aa"], p["d2ab"])
+    Raa, Rab, gn2 = ctx.residual(p["h"], p["V"], p["gamma"], p["d2aa"], p["d2ab"], p["N"] // 2)
+    assert rel(cpu(Raa), raa) < TOL64 and rel(cpu(Rab), rab) < TOL64
+
+
 def test_deterministic(ctx):
     p = PROBLEMS["r10"]()
     a = ctx.residual(p["h"], p["V"], p["gamma"], p["d2aa"], p["d2ab"], p["N"] // 2)
