@@ -53,6 +53,18 @@ def parse():
     return ap.parse_args()
 
 
+# GEMM tile shapes (BM, BN, BK) per configuration index, as instantiated in gemm.hip
+TILE_SHAPES = {"fp64": [(128, 128, 16), (64, 64, 16), (128, 64, 16)],
+               "fp32": [(128, 128, 32), (64, 64, 32), (128, 64, 32)],
+               "bf16x3": [(128, 128, 32), (64, 64, 32), (128, 64, 32)]}
+TRAITS = {"fp64": "TrF64", "fp32": "TrF32", "bf16x3": "TrBF16x3"}
+
+
+def gemm_kernel_name(prec, cfg):
+    bm, bn, bk = TILE_SHAPES[prec][cfg]
+    return f"acse::gemm_nt_kernel<acse::{TRAITS[prec]}, {bm}, {bn}, {bk}>"
+
+
 def src_hash():
     with open(GEMM_SRC, "rb") as f:
         return hashlib.sha256(f.read()).hexdigest()[:16]
@@ -172,8 +184,10 @@ def main():
     traffic = None
     if os.path.exists(TRAFFIC):
         t = json.load(open(TRAFFIC))
-        if t.get("gemm_src_sha256_16") == src_hash() and t.get("precision") == head:
-            traffic = t.get("bytes_per_launch")
+        k = t.get("kernels", {}).get(head)
+        if (t.get("gemm_src_sha256_16") == src_hash() and k is not None
+                and k.get("kernel") == gemm_kernel_name(head, hr["tile_config"])):
+            traffic = k.get("bytes_per_launch")
     line = {
         "metric": "ACSE residual evals/s + TFLOP/s at r=50: FP64 vs mixed at |dE|<1e-7 Eh",
         "value": hr["steps_per_s"],
@@ -194,7 +208,8 @@ def main():
         "roofline": {"bound": "mfma", "achieved": hr["gemm_tflops"], "peak": PEAK_TFLOPS[head],
                      "unit": "TFLOP/s", "frac": hr["gemm_tflops"] / PEAK_TFLOPS[head],
                      "traffic": traffic,
-                     "kernel": "grouped pair-index GEMM (5 x r^2 x r^2 x r^2 per launch)"},
+                     "kernel": gemm_kernel_name(head, hr["tile_config"]) +
+                               " (grouped: 5 x r^2 x r^2 x r^2 products per launch)"},
         "residual_only_evals_per_s": hr["residual_evals_per_s"],
         "modes": results,
     }

@@ -41,6 +41,9 @@ __device__ inline typename Tr::Acc acc_zero() {
   return a;
 }
 
+constexpr int kNumXcd = 8;
+constexpr int kGroupM = 8;
+
 template <class Tr, int BM, int BN, int BK>
 __global__ void __launch_bounds__(256)
 gemm_nt_kernel(const GemmBatch batch) {
@@ -62,7 +65,13 @@ gemm_nt_kernel(const GemmBatch batch) {
   __shared__ __attribute__((aligned(16))) T Bs[2][NP][BN * LDK];
 
   // --- which problem / tile / K chunk --------------------------------------
-  const int bid = blockIdx.x;
+  // Workgroups are dispatched round-robin over the 8 XCDs, each with its own
+  // L2: remap so every XCD works through a contiguous range of logical tiles.
+  const int total = batch.total_tiles;
+  const int hw = blockIdx.x;
+  const int xcd = hw % kNumXcd, kx = hw / kNumXcd;
+  const int q8 = total / kNumXcd, rem8 = total % kNumXcd;
+  const int bid = xcd < rem8 ? xcd * (q8 + 1) + kx : rem8 * (q8 + 1) + (xcd - rem8) * q8 + kx;
   int g = 0;
 #pragma unroll
   for (int q = 1; q < kMaxGemmProbs; ++q)
@@ -72,8 +81,15 @@ gemm_nt_kernel(const GemmBatch batch) {
   const int per_split = P.tiles_m * P.tiles_n;
   const int split = local / per_split;
   local -= split * per_split;
-  const int tm = local / P.tiles_n;
-  const int tn = local - tm * P.tiles_n;
+  // grouped order: kGroupM tile rows sweep the columns together so the
+  // resident workgroups share A and B panel slabs in L2
+  const int in_group = kGroupM * P.tiles_n;
+  const int group = local / in_group;
+  const int first_m = group * kGroupM;
+  const int gsz = min(P.tiles_m - first_m, kGroupM);
+  const int lg = local - group * in_group;
+  const int tm = first_m + lg % gsz;
+  const int tn = lg / gsz;
   const int m0 = tm * BM, n0 = tn * BN;
   const int kbeg = split * P.kchunk;
   const int kend = min(P.Kp, kbeg + P.kchunk);
