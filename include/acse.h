@@ -134,6 +134,27 @@ acse_status acse_step(acse_ctx ctx, acse_problem *prob, double eps, const acse_o
                       double *R_aa, double *R_ab, double *U_aa, double *U_ab,
                       double *E_host, double *norm2_host);
 
+/* Hand-written adjoint (vector-Jacobian product) of the residual of Eq. (4):
+ * given a cotangent (Rbar_aa, Rbar_ab) on (R_aa, R_ab), writes the gradients of
+ * L = <Rbar_aa, R_aa> + <Rbar_ab, R_ab> with respect to h, V, d1, d2aa and
+ * d2ab (device arrays of the same shapes).  The forward intermediates are
+ * recomputed, not stored.  Each gradient is projected onto the symmetry
+ * subspace of its input (h, d1 symmetric; V 8-fold symmetric; d2aa
+ * antisymmetric in both pairs and Hermitian; d2ab Hermitian and symmetric
+ * under (pq)(rs) -> (qp)(sr)), which is what finite differences along
+ * symmetry-respecting directions measure.  The contractions run in
+ * opts->precision; accumulation of the gradients is FP64.  The first call
+ * allocates the adjoint workspace (36 r_max^4 doubles plus 12 pair-index
+ * operand buffers), kept until acse_destroy.  Errors as acse_residual. */
+acse_status acse_residual_vjp(acse_ctx ctx, const acse_problem *prob, const acse_options *opts,
+                              const double *Rbar_aa, const double *Rbar_ab, double *h_bar,
+                              double *V_bar, double *d1_bar, double *d2aa_bar, double *d2ab_bar);
+
+/* Adjoint of the energy E = Tr(K 2D): gradients of Ebar * E with respect to
+ * h, V, d2aa, d2ab (projected as above).  d1 does not enter E. */
+acse_status acse_energy_vjp(acse_ctx ctx, const acse_problem *prob, double Ebar, double *h_bar,
+                            double *V_bar, double *d2aa_bar, double *d2ab_bar);
+
 /* Stage timing with HIP events recorded on the context's stream.  Stages:
  *   0  RDM-side operands (W = Gamma2 - 2/3 Gamma1^Gamma1 and its layouts)
  *   1  fold of the reduced Hamiltonian (Eq. (2))

@@ -21,6 +21,9 @@ the plainest form available:
   formed), and a single-element evaluator for sampled checks at large r.
 * ``step``     -- the Euler update of Eq. (9), the active-active mask, trace
   restoration, the 1-RDM contraction and the energy Tr(K 2D).
+* ``adjoint``  -- vector-Jacobian products of the residual and the energy by
+  reverse-mode differentiation of the tier-B torch forward, projected onto
+  the symmetry subspaces of the inputs.
 
 All arithmetic is float64.  Readings of the paper where it is silent, garbled
 or self-inconsistent are stated in the docstrings where they are used.

@@ -31,7 +31,8 @@ STATUS = {0: "ACSE_OK", 1: "ACSE_ERR_ARG", 2: "ACSE_ERR_SHAPE", 3: "ACSE_ERR_ALI
 # Every function declared in include/acse.h.
 EXPORTS = ("acse_create", "acse_destroy", "acse_set_stream", "acse_residual", "acse_update_map",
            "acse_energy", "acse_step", "acse_status_str", "acse_last_error",
-           "acse_workspace_bytes", "acse_profile_enable", "acse_profile_read", "acse_autotune")
+           "acse_workspace_bytes", "acse_profile_enable", "acse_profile_read", "acse_autotune",
+           "acse_residual_vjp", "acse_energy_vjp")
 NUM_TILE_CONFIGS = 3
 NUM_STAGES = 6
 STAGES = ("rdm_operands", "fold", "transforms", "gemm", "assembly", "step_tail")
@@ -70,6 +71,10 @@ _sig = {
     "acse_profile_read": (ctypes.c_int, [_P, ctypes.POINTER(ProfileData)]),
     "acse_autotune": (ctypes.c_int, [_P, ctypes.POINTER(Problem), ctypes.POINTER(Options),
                                      ctypes.POINTER(ctypes.c_int32), _D]),
+    "acse_residual_vjp": (ctypes.c_int, [_P, ctypes.POINTER(Problem), ctypes.POINTER(Options),
+                                         _P, _P, _P, _P, _P, _P, _P]),
+    "acse_energy_vjp": (ctypes.c_int, [_P, ctypes.POINTER(Problem), ctypes.c_double,
+                                       _P, _P, _P, _P]),
 }
 for _name, (_res, _args) in _sig.items():
     _fn = getattr(_lib, _name)
@@ -226,6 +231,80 @@ class Context:
         if return_ru:
             extra = dict(R_aa=bufs[0], R_ab=bufs[1], U_aa=bufs[2], U_ab=bufs[3])
         return dict(d1=t[2], d2aa=t[3], d2ab=t[4], energy=E, norm2=n2, **extra)
+
+    def residual_vjp_raw(self, prob, opts, Rbar_aa, Rbar_ab, h_bar, V_bar, d1_bar, d2aa_bar, d2ab_bar):
+        self._check(_lib.acse_residual_vjp(self._h, ctypes.byref(prob), ctypes.byref(opts),
+                                           _ptr(Rbar_aa), _ptr(Rbar_ab), _ptr(h_bar), _ptr(V_bar),
+                                           _ptr(d1_bar), _ptr(d2aa_bar), _ptr(d2ab_bar)))
+
+    def residual_vjp(self, h, V, d1, d2aa, d2ab, n_alpha, Rbar_aa, Rbar_ab, precision="fp64", tile=-1):
+        """Cotangents (h, V, d1, d2aa, d2ab) of <Rbar, R> for the residual of Eq. (4),
+        projected onto the symmetry subspace of each input."""
+        prob, keep = self.problem(h, V, d1, d2aa, d2ab, n_alpha)
+        rb = [_dev(x, self.device) for x in (Rbar_aa, Rbar_ab)]
+        out = [torch.empty_like(x) for x in keep]
+        self.residual_vjp_raw(prob, self.options(precision, None, tile), *rb, *out)
+        return tuple(out)
+
+    def energy_vjp_raw(self, prob, Ebar, h_bar, V_bar, d2aa_bar, d2ab_bar):
+        self._check(_lib.acse_energy_vjp(self._h, ctypes.byref(prob), float(Ebar), _ptr(h_bar),
+                                         _ptr(V_bar), _ptr(d2aa_bar), _ptr(d2ab_bar)))
+
+    def energy_vjp(self, h, V, d2aa, d2ab, n_alpha, Ebar=1.0):
+        """Cotangents (h, V, d2aa, d2ab) of Ebar * E, E = Tr(K 2D), projected."""
+        r = h.shape[0]
+        prob, keep = self.problem(h, V, torch.zeros(r, r), d2aa, d2ab, n_alpha)
+        out = [torch.empty_like(keep[q]) for q in (0, 1, 3, 4)]
+        self.energy_vjp_raw(prob, Ebar, *out)
+        return tuple(out)
+
+
+class ACSEResidual(torch.autograd.Function):
+    """R = F(K) of Eq. (4) as an autograd function with the hand-written adjoint.
+
+    ``ACSEResidual.apply(ctx, h, V, d1, d2aa, d2ab, n_alpha, precision)`` returns
+    (R_aa, R_ab).  The gradients are those of the loss restricted to the
+    symmetric inputs: each is projected onto its input's symmetry subspace
+    (h, d1 symmetric; V with the 8-fold symmetry of (pq|rs); d2aa antisymmetric
+    within each pair and Hermitian; d2ab Hermitian and pair-exchange symmetric).
+    """
+
+    @staticmethod
+    def forward(fctx, ctx, h, V, d1, d2aa, d2ab, n_alpha, precision="fp64"):
+        R_aa, R_ab, _ = ctx.residual(h, V, d1, d2aa, d2ab, n_alpha, precision)
+        fctx.acse = (ctx, n_alpha, precision)
+        fctx.save_for_backward(h, V, d1, d2aa, d2ab)
+        return R_aa, R_ab
+
+    @staticmethod
+    def backward(fctx, Rb_aa, Rb_ab):
+        ctx, n_alpha, precision = fctx.acse
+        h, V, d1, d2aa, d2ab = fctx.saved_tensors
+        r = h.shape[0]
+        zero = torch.zeros((r, r, r, r), dtype=torch.float64, device=ctx.device)
+        Rb_aa = zero if Rb_aa is None else Rb_aa
+        Rb_ab = zero if Rb_ab is None else Rb_ab
+        g = ctx.residual_vjp(h, V, d1, d2aa, d2ab, n_alpha, Rb_aa, Rb_ab, precision)
+        return (None,) + tuple(x.to(t.dtype) for x, t in zip(g, (h, V, d1, d2aa, d2ab))) + (None, None)
+
+
+class ACSEEnergy(torch.autograd.Function):
+    """E = Tr(K 2D) (Eq. (2), Eq. (6)) with its adjoint; gradients projected as in
+    ``ACSEResidual``.  ``ACSEEnergy.apply(ctx, h, V, d2aa, d2ab, n_alpha)``."""
+
+    @staticmethod
+    def forward(fctx, ctx, h, V, d2aa, d2ab, n_alpha):
+        E = ctx.energy(h, V, d2aa, d2ab, n_alpha)
+        fctx.acse = (ctx, n_alpha)
+        fctx.save_for_backward(h, V, d2aa, d2ab)
+        return torch.tensor(E, dtype=torch.float64, device=ctx.device)
+
+    @staticmethod
+    def backward(fctx, Eb):
+        ctx, n_alpha = fctx.acse
+        h, V, d2aa, d2ab = fctx.saved_tensors
+        g = ctx.energy_vjp(h, V, d2aa, d2ab, n_alpha, float(Eb))
+        return (None,) + tuple(x.to(t.dtype) for x, t in zip(g, (h, V, d2aa, d2ab))) + (None,)
 
 
 def status_str(code):

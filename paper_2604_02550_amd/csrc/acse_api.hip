@@ -25,6 +25,7 @@
 
 #include "../../include/acse.h"
 #include "tensor_ops.h"
+#include "vjp.h"
 
 using namespace acse;
 
@@ -60,6 +61,12 @@ struct acse_ctx_s {
   double ms[ACSE_NUM_STAGES] = {};
   int64_t count[ACSE_NUM_STAGES] = {};
   std::map<std::pair<int, int>, int> tuned;  // (r, precision) -> tile configuration
+  // adjoint workspace (allocated by the first VJP call)
+  void *vbase = nullptr;
+  int64_t vbytes = 0;
+  double *vnat[36] = {};
+  char *vop[12] = {};
+  double *vsmall = nullptr;  // gb, tb, fb, I, hb_raw (r_max^2 each)
 };
 
 namespace {
@@ -393,6 +400,7 @@ acse_status acse_destroy(acse_ctx ctx) {
   (void)hipStreamSynchronize(ctx->stream);
   for (auto &q : ctx->recs) { (void)hipEventDestroy(q.a); (void)hipEventDestroy(q.b); }
   for (auto e : ctx->pool) (void)hipEventDestroy(e);
+  if (ctx->vbase) (void)hipFree(ctx->vbase);
   (void)hipFree(ctx->base);
   delete ctx;
   return ACSE_OK;
@@ -562,3 +570,367 @@ acse_status acse_step(acse_ctx ctx, acse_problem *prob, double eps, const acse_o
 }
 
 }  // extern "C"
+
+// ===========================================================================
+// Adjoint of the residual map (VJP).  The steps mirror the forward chain in
+// reverse; every product of the forward has its two adjoint products here.
+// ===========================================================================
+namespace {
+
+acse_status ensure_vjp_ws(acse_ctx c) {
+  if (c->vbase) return ACSE_OK;
+  const int64_t n4 = (int64_t)c->r_max * c->r_max * c->r_max * c->r_max;
+  const int64_t r2 = (int64_t)c->r_max * c->r_max;
+  const int64_t nat = round_up(n4 * 8, 256);
+  const int64_t opb = c->op_bytes;
+  const int64_t small = 5 * round_up(r2 * 8, 256);
+  const int64_t bytes = 36 * nat + 12 * opb + small;
+  if (hipMalloc(&c->vbase, bytes) != hipSuccess) {
+    (void)hipGetLastError();
+    c->vbase = nullptr;
+    return fail(c, ACSE_ERR_NOMEM, "adjoint workspace allocation failed");
+  }
+  c->vbytes = bytes;
+  char *p = static_cast<char *>(c->vbase);
+  for (int q = 0; q < 36; ++q) { c->vnat[q] = reinterpret_cast<double *>(p); p += nat; }
+  for (int q = 0; q < 12; ++q) { c->vop[q] = p; p += opb; }
+  c->vsmall = reinterpret_cast<double *>(p);
+  return ACSE_OK;
+}
+
+struct Nat4 {
+  int64_t S[4];
+  explicit Nat4(int r) {
+    S[3] = 1; S[2] = r; S[1] = (int64_t)r * r; S[0] = (int64_t)r * r * r;
+  }
+  // strides of the source for destination index positions given by the source
+  // positions they come from
+  void map(const int m[4], int64_t out[4]) const {
+    for (int d = 0; d < 4; ++d) out[d] = S[m[d]];
+  }
+};
+
+}  // namespace
+
+extern "C" acse_status acse_residual_vjp(acse_ctx ctx, const acse_problem *prob,
+                                         const acse_options *opts, const double *Rbar_aa,
+                                         const double *Rbar_ab, double *h_bar, double *V_bar,
+                                         double *d1_bar, double *d2aa_bar, double *d2ab_bar) {
+  acse_status st = validate(ctx, prob, opts);
+  if (st != ACSE_OK) return st;
+  for (const void *q : {static_cast<const void *>(Rbar_aa), static_cast<const void *>(Rbar_ab),
+                        static_cast<const void *>(h_bar), static_cast<const void *>(V_bar),
+                        static_cast<const void *>(d1_bar), static_cast<const void *>(d2aa_bar),
+                        static_cast<const void *>(d2ab_bar)})
+    if ((st = check_out(ctx, q, "VJP array")) != ACSE_OK) return st;
+  HIP_TRY(ctx, hipSetDevice(ctx->device));
+  if ((st = ensure_vjp_ws(ctx)) != ACSE_OK) return st;
+
+  const int r = prob->r;
+  const int N = prob->n_alpha + prob->n_beta;
+  const int64_t r2 = (int64_t)r * r, r3 = r2 * r;
+  const int ld = (int)op_ld(r);
+  const int64_t Mp = op_rows(r);
+  const GemmPrec prec = prec_of(opts);
+  const double *g = prob->d1;
+  Workspace &w = ctx->ws;
+  hipStream_t s = ctx->stream;
+  const Nat4 nat(r);
+  double **V = ctx->vnat;
+  double *gb = ctx->vsmall, *tb = gb + r2, *fb = tb + r2, *Id = fb + r2, *hb_raw = Id + r2;
+  // operand buffers of the adjoint GEMMs
+  auto vop = [&](int q) {
+    OperandRef o{ctx->vop[q], nullptr};
+    if (prec == GEMM_BF16X3) o.lo = ctx->vop[q] + Mp * ld * 2;
+    return o;
+  };
+  // natural r^4 destination
+  auto natref = [&](double *p) { return OperandRef{p, nullptr}; };
+  auto permute = [&](GemmPrec pr, const OperandRef &dst, bool operand_layout, const double *s1,
+                     const int m1[4], double c1, const double *s2, const int m2[4], double c2,
+                     int acc) -> hipError_t {
+    PermArgs a{};
+    a.r = r;
+    a.rows = operand_layout ? Mp : r2;
+    a.ld = operand_layout ? ld : r2;
+    a.src1 = s1;
+    nat.map(m1, a.s1);
+    a.c1 = c1;
+    a.src2 = s2;
+    if (s2) nat.map(m2, a.s2);
+    a.c2 = c2;
+    a.accumulate = acc;
+    return launch_permute4(pr, a, dst, s);
+  };
+  const int ID[4] = {0, 1, 2, 3};
+  auto mode = [&](const double *in1, const double *in2, double c2, const double *M, int tr,
+                  int64_t A, int64_t Bn, double alpha, double *out, int64_t adiv, int64_t so1,
+                  int64_t so0, int64_t sx, int64_t sb, int cols_fast, int acc) -> hipError_t {
+    ModeArgs m = mode_base(r, M);
+    m.A = A; m.Bn = Bn; m.in1 = in1; m.in2 = in2; m.c2 = c2; m.transpose_m = tr;
+    m.alpha = alpha; m.adiv = adiv; m.so1 = so1; m.so0 = so0; m.sx = sx; m.sb = sb;
+    m.out_cols_fast = cols_fast; m.accumulate = acc;
+    return launch_mode(GEMM_F64, m, OperandRef{out, nullptr}, s);
+  };
+  auto term = [&](const double *T, int px, int py, int pu, int pv, const double *M, double c) {
+    ContractTerm t{};
+    t.T = T; t.sx = nat.S[px]; t.sy = nat.S[py]; t.su = nat.S[pu]; t.sv = nat.S[pv]; t.M = M; t.c = c;
+    return t;
+  };
+  auto contract = [&](std::initializer_list<ContractTerm> terms, double *out, int acc) -> hipError_t {
+    ContractArgs a{};
+    for (const ContractTerm &t : terms) a.term[a.nterms++] = t;
+    return launch_contract42(r, a, out, acc, s);
+  };
+
+  // ---------------- forward recompute (natural layouts) -------------------
+  if ((st = prep_rdm_operands(ctx, prob, prec)) != ACSE_OK) return st;
+  HIP_TRY(ctx, launch_fold(r, N, prob->h, prob->V, w.Aaa, w.Aab, s));
+  HIP_TRY(ctx, launch_f(r, w.Aaa, w.Aab, g, w.fpart, w.f, s));
+  HIP_TRY(ctx, launch_t(r, w.Waa, w.Aaa, w.Wab, w.Aab, w.tpart, w.t, s));
+  for (int b = 0; b < 2; ++b)
+    HIP_TRY(ctx, mode(b ? w.Aab : w.Aaa, nullptr, 0.0, g, 1, r, r2, 1.0, b ? w.Hab : w.Haa, 1, r3, 0,
+                      r2, 1, 1, 0));
+  HIP_TRY(ctx, launch_g2(prec, r, ld, w.Aaa, w.Aab, w.Haa, w.Hab, w.f, w.G2aa, w.G2ab, vop(0), vop(1), s));
+  double *Baa = V[0], *Bab = V[1], *Lp = V[2], *Lm = V[3], *L3 = V[4], *Rp = V[5], *Rm = V[6], *R3 = V[7];
+  HIP_TRY(ctx, permute(GEMM_F64, natref(Baa), false, w.Aaa, ID, 1.0, w.G2aa, ID, -1.0, 0));
+  HIP_TRY(ctx, permute(GEMM_F64, natref(Bab), false, w.Aab, ID, 1.0, w.G2ab, ID, -1.0, 0));
+  // L+-[k,i,p,s] = sum_r g[i,r] (A_aa +- A_ab)[k,p,r,s];  L3[k,j,p,s] = sum_r g[j,r] A_ab[k,p,s,r]
+  HIP_TRY(ctx, mode(w.Aaa, w.Aab, 1.0, g, 0, r2, r, 1.0, Lp, r, r3, r, r2, 1, 1, 0));
+  HIP_TRY(ctx, mode(w.Aaa, w.Aab, -1.0, g, 0, r2, r, 1.0, Lm, r, r3, r, r2, 1, 1, 0));
+  HIP_TRY(ctx, mode(w.Aab, nullptr, 0.0, g, 0, r3, 1, 1.0, L3, r2, r3, 1, r2, 0, 1, 0));
+  {  // R+-[j,l,p,s] = W_aa[j,p,s,l] -+ W_ab[j,p,l,s];  R3[i,l,p,s] = W_ab[i,p,s,l]
+    const int ma[4] = {0, 3, 1, 2}, mb[4] = {0, 2, 1, 3};
+    HIP_TRY(ctx, permute(GEMM_F64, natref(Rp), false, w.Waa, ma, 1.0, w.Wab, mb, -1.0, 0));
+    HIP_TRY(ctx, permute(GEMM_F64, natref(Rm), false, w.Waa, ma, 1.0, w.Wab, mb, 1.0, 0));
+    HIP_TRY(ctx, permute(GEMM_F64, natref(R3), false, w.Wab, ma, 1.0, nullptr, ID, 0.0, 0));
+  }
+
+  // ---------------- backward ----------------------------------------------
+  double *Sbaa = V[8], *Sbab = V[9], *Ppb = V[10], *Pmb = V[11], *E3b = V[12];
+  double *Lpb = V[13], *Lmb = V[14], *L3b = V[15], *Rpb = V[16], *Rmb = V[17], *R3b = V[18];
+  double *Gbaa = V[19], *Gbab = V[20], *Bbaa = V[21], *Bbab = V[22], *Maa = V[23], *Mab = V[24];
+  double *G2baa = V[25], *G2bab = V[26], *Abaa = V[27], *Abab = V[28], *Wbaa = V[29], *Wbab = V[30];
+  double *T1 = V[31], *T2 = V[32], *T3 = V[33], *T4 = V[34], *Vraw = V[35];
+  HIP_TRY(ctx, launch_fill(r2, 0.0, gb, s));
+  HIP_TRY(ctx, launch_identity(r, Id, s));
+  // S-bar = R-bar - R-bar^T  (R = S - S^T)
+  {
+    const int tr[4] = {2, 3, 0, 1};
+    HIP_TRY(ctx, permute(GEMM_F64, natref(Sbaa), false, Rbar_aa, ID, 1.0, Rbar_aa, tr, -1.0, 0));
+    HIP_TRY(ctx, permute(GEMM_F64, natref(Sbab), false, Rbar_ab, ID, 1.0, Rbar_ab, tr, -1.0, 0));
+  }
+  // gamma-t terms: t-bar and gamma-bar (S_aa carries -gt_aa, S_ab carries +gt_ab)
+  HIP_TRY(ctx, contract({term(Sbaa, 1, 2, 0, 3, g, -1.0), term(Sbaa, 0, 2, 1, 3, g, 1.0),
+                         term(Sbaa, 1, 3, 0, 2, g, 1.0), term(Sbaa, 0, 3, 1, 2, g, -1.0),
+                         term(Sbab, 0, 2, 1, 3, g, 1.0), term(Sbab, 1, 3, 0, 2, g, 1.0)},
+                        tb, 0));
+  HIP_TRY(ctx, contract({term(Sbaa, 0, 3, 1, 2, w.t, -1.0), term(Sbaa, 1, 3, 0, 2, w.t, 1.0),
+                         term(Sbaa, 0, 2, 1, 3, w.t, 1.0), term(Sbaa, 1, 2, 0, 3, w.t, -1.0),
+                         term(Sbab, 1, 3, 0, 2, w.t, 1.0), term(Sbab, 0, 2, 1, 3, w.t, 1.0)},
+                        gb, 1));
+  HIP_TRY(ctx, launch_vjp_pe(r, Sbaa, Sbab, Ppb, Pmb, E3b, s));
+
+  auto gemm_set = [&](GemmBatch &b, int q, int ia, int ib, double alpha, double *C, const int om[4]) {
+    GemmProb &P = b.p[q];
+    OperandRef a = vop(ia), bb = vop(ib);
+    P.A = a.hi; P.A2 = a.lo; P.B = bb.hi; P.B2 = bb.lo;
+    P.C = C; P.alpha = alpha;
+    P.M = (int)r2; P.N = (int)r2; P.Kp = ld; P.ld = ld; P.rdiv = r;
+    // output (m/r, m%r, n/r, n%r) -> natural positions om[0..3] of the result
+    P.sm1 = nat.S[om[0]]; P.sm0 = nat.S[om[1]]; P.sn1 = nat.S[om[2]]; P.sn0 = nat.S[om[3]];
+    P.ksplit = 1; P.kchunk = ld; P.accumulate = 0;
+  };
+  const int use_cfg = opts && opts->tile >= 0 ? opts->tile : gemm_default_cfg(prec, (int)r2, (int)r2);
+  {  // particle-hole adjoint products
+    // L+b[(k,i),(p,s)] = sum_(j,l) P+b[i,j,k,l] R+[j,l,p,s];  R+b[(j,l),(p,s)] = sum_(k,i) P+b L+[k,i,p,s]
+    const int Akijl[4] = {2, 0, 1, 3}, Ajlki[4] = {1, 3, 2, 0};
+    const int Bps_jl[4] = {2, 3, 0, 1};   // R[j,l,p,s] as rows (p,s), cols (j,l)
+    const int Bps_ki[4] = {2, 3, 0, 1};   // L[k,i,p,s] as rows (p,s), cols (k,i)
+    const int Akjil[4] = {2, 1, 0, 3}, Ailkj[4] = {0, 3, 2, 1};
+    HIP_TRY(ctx, permute(prec, vop(0), true, Ppb, Akijl, 1.0, nullptr, ID, 0.0, 0));
+    HIP_TRY(ctx, permute(prec, vop(1), true, Rp, Bps_jl, 1.0, nullptr, ID, 0.0, 0));
+    HIP_TRY(ctx, permute(prec, vop(2), true, Ppb, Ajlki, 1.0, nullptr, ID, 0.0, 0));
+    HIP_TRY(ctx, permute(prec, vop(3), true, Lp, Bps_ki, 1.0, nullptr, ID, 0.0, 0));
+    HIP_TRY(ctx, permute(prec, vop(4), true, Pmb, Akijl, 1.0, nullptr, ID, 0.0, 0));
+    HIP_TRY(ctx, permute(prec, vop(5), true, Rm, Bps_jl, 1.0, nullptr, ID, 0.0, 0));
+    HIP_TRY(ctx, permute(prec, vop(6), true, Pmb, Ajlki, 1.0, nullptr, ID, 0.0, 0));
+    HIP_TRY(ctx, permute(prec, vop(7), true, Lm, Bps_ki, 1.0, nullptr, ID, 0.0, 0));
+    // L3b[(k,j),(p,s)] = -2 sum_(i,l) E3b[i,j,k,l] R3[i,l,p,s];  R3b[(i,l),(p,s)] = -2 sum_(k,j) E3b L3[k,j,p,s]
+    HIP_TRY(ctx, permute(prec, vop(8), true, E3b, Akjil, 1.0, nullptr, ID, 0.0, 0));
+    HIP_TRY(ctx, permute(prec, vop(9), true, R3, Bps_jl, 1.0, nullptr, ID, 0.0, 0));
+    HIP_TRY(ctx, permute(prec, vop(10), true, E3b, Ailkj, 1.0, nullptr, ID, 0.0, 0));
+    HIP_TRY(ctx, permute(prec, vop(11), true, L3, Bps_ki, 1.0, nullptr, ID, 0.0, 0));
+    GemmBatch b{};
+    b.count = 6;
+    gemm_set(b, 0, 0, 1, 1.0, Lpb, ID);
+    gemm_set(b, 1, 2, 3, 1.0, Rpb, ID);
+    gemm_set(b, 2, 4, 5, 1.0, Lmb, ID);
+    gemm_set(b, 3, 6, 7, 1.0, Rmb, ID);
+    gemm_set(b, 4, 8, 9, -2.0, L3b, ID);
+    gemm_set(b, 5, 10, 11, -2.0, R3b, ID);
+    HIP_TRY(ctx, gemm_launch(prec, use_cfg, b, s));
+  }
+  {  // particle-particle adjoint products
+    // G-bar = Z-bar B^T-products:  Gb[(ij),(rs)] = sum_(kl) Sb[ij,kl] B[kl,rs]
+    //                              Bb[(kl),(rs)] = sum_(ij) Sb[ij,kl] Gamma2[ij,rs]
+    //                              M[(ij),(rs)]  = sum_(kl) Sb[ij,kl] G2[kl,rs]
+    const int Akl_ij[4] = {2, 3, 0, 1};   // Sb[i,j,k,l] as rows (k,l), cols (i,j)
+    const int Brs_kl[4] = {2, 3, 0, 1};   // X[k,l,r,s] as rows (r,s), cols (k,l)
+    // aa block
+    HIP_TRY(ctx, permute(prec, vop(0), true, Sbaa, ID, 1.0, nullptr, ID, 0.0, 0));
+    HIP_TRY(ctx, permute(prec, vop(1), true, Sbaa, Akl_ij, 1.0, nullptr, ID, 0.0, 0));
+    HIP_TRY(ctx, permute(prec, vop(2), true, Baa, Brs_kl, 1.0, nullptr, ID, 0.0, 0));
+    HIP_TRY(ctx, permute(prec, vop(3), true, prob->d2aa, Brs_kl, 1.0, nullptr, ID, 0.0, 0));
+    HIP_TRY(ctx, permute(prec, vop(4), true, w.G2aa, Brs_kl, 1.0, nullptr, ID, 0.0, 0));
+    // ab block
+    HIP_TRY(ctx, permute(prec, vop(5), true, Sbab, ID, 1.0, nullptr, ID, 0.0, 0));
+    HIP_TRY(ctx, permute(prec, vop(6), true, Sbab, Akl_ij, 1.0, nullptr, ID, 0.0, 0));
+    HIP_TRY(ctx, permute(prec, vop(7), true, Bab, Brs_kl, 1.0, nullptr, ID, 0.0, 0));
+    HIP_TRY(ctx, permute(prec, vop(8), true, prob->d2ab, Brs_kl, 1.0, nullptr, ID, 0.0, 0));
+    HIP_TRY(ctx, permute(prec, vop(9), true, w.G2ab, Brs_kl, 1.0, nullptr, ID, 0.0, 0));
+    GemmBatch b{};
+    b.count = 6;
+    gemm_set(b, 0, 0, 2, 1.0, Gbaa, ID);
+    gemm_set(b, 1, 1, 3, 2.0, Bbaa, ID);   // Gamma2_aa = 2 d2aa
+    gemm_set(b, 2, 0, 4, 1.0, Maa, ID);
+    gemm_set(b, 3, 5, 7, 2.0, Gbab, ID);
+    gemm_set(b, 4, 6, 8, 4.0, Bbab, ID);   // 2 * Gamma2_ab = 4 d2ab
+    gemm_set(b, 5, 5, 9, 1.0, Mab, ID);
+    HIP_TRY(ctx, gemm_launch(prec, use_cfg, b, s));
+  }
+  // G2-bar = 4/3 (gamma x gamma) S-bar^T - B-bar;  A-bar += B-bar
+  {
+    const int tr[4] = {2, 3, 0, 1};
+    for (int b = 0; b < 2; ++b) {
+      const double *Sb = b ? Sbab : Sbaa;
+      double *G2b = b ? G2bab : G2baa;
+      const double *Bb = b ? Bbab : Bbaa;
+      double *Ab = b ? Abab : Abaa;
+      HIP_TRY(ctx, permute(GEMM_F64, natref(T1), false, Sb, tr, 1.0, nullptr, ID, 0.0, 0));  // [k,l,i,j]
+      // T2[k,l,i,s] = sum_j g[j,s] T1[k,l,i,j]
+      HIP_TRY(ctx, mode(T1, nullptr, 0.0, g, 1, r3, 1, 1.0, T2, 1, r, 0, 1, 0, 0, 0));
+      // G2b[k,l,r,s] = 4/3 sum_i g[i,r] T2[k,l,i,s]
+      HIP_TRY(ctx, mode(T2, nullptr, 0.0, g, 1, r2, r, 4.0 / 3.0, G2b, 1, r2, 0, r, 1, 1, 0));
+      HIP_TRY(ctx, permute(GEMM_F64, natref(G2b), false, Bb, ID, -1.0, nullptr, ID, 0.0, 1));
+      HIP_TRY(ctx, permute(GEMM_F64, natref(Ab), false, Bb, ID, 1.0, nullptr, ID, 0.0, 0));
+    }
+  }
+  // gamma-bar from M = S-bar G2:  4/3 (sum_js M[i,j,r,s] g[j,s] + sum_ir M[i,j,r,s] g[i,r])
+  HIP_TRY(ctx, contract({term(Maa, 0, 2, 1, 3, g, 4.0 / 3.0), term(Maa, 1, 3, 0, 2, g, 4.0 / 3.0),
+                         term(Mab, 0, 2, 1, 3, g, 4.0 / 3.0), term(Mab, 1, 3, 0, 2, g, 4.0 / 3.0)},
+                        gb, 1));
+  // H-bar and f-bar from G2-bar
+  {
+    const int lk_aa[4] = {1, 0, 2, 3}, lk_ab[4] = {1, 0, 3, 2};
+    HIP_TRY(ctx, permute(GEMM_F64, natref(Ppb), false, G2baa, ID, 1.0, G2baa, lk_aa, -1.0, 0));  // Hbaa
+    HIP_TRY(ctx, permute(GEMM_F64, natref(Pmb), false, G2bab, ID, 1.0, G2bab, lk_ab, 1.0, 0));   // Hbab
+  }
+  double *Hbaa = Ppb, *Hbab = Pmb;
+  HIP_TRY(ctx, contract({term(G2baa, 0, 2, 1, 3, Id, 1.0), term(G2baa, 0, 3, 1, 2, Id, -1.0),
+                         term(G2baa, 1, 2, 0, 3, Id, -1.0), term(G2baa, 1, 3, 0, 2, Id, 1.0),
+                         term(G2bab, 0, 2, 1, 3, Id, 1.0), term(G2bab, 1, 3, 0, 2, Id, 1.0)},
+                        fb, 0));
+  // H = A g: A-bar[k,p,(rs)] += sum_l g[p,l] H-bar[k,l,(rs)];  g-bar[p,l] += sum A[k,p,r,s] H-bar[k,l,r,s]
+  for (int b = 0; b < 2; ++b)
+    HIP_TRY(ctx, mode(b ? Hbab : Hbaa, nullptr, 0.0, g, 0, r, r2, 1.0, b ? Abab : Abaa, 1, r3, 0, r2, 1, 1, 1));
+  {
+    const int lead1[4] = {1, 0, 2, 3};   // [p][k,r,s] from X[k,p,r,s]
+    HIP_TRY(ctx, permute(GEMM_F64, natref(T1), false, w.Aaa, lead1, 1.0, nullptr, ID, 0.0, 0));
+    HIP_TRY(ctx, permute(GEMM_F64, natref(T2), false, Hbaa, lead1, 1.0, nullptr, ID, 0.0, 0));
+    HIP_TRY(ctx, permute(GEMM_F64, natref(T3), false, w.Aab, lead1, 1.0, nullptr, ID, 0.0, 0));
+    HIP_TRY(ctx, permute(GEMM_F64, natref(T4), false, Hbab, lead1, 1.0, nullptr, ID, 0.0, 0));
+    HIP_TRY(ctx, launch_gram(r, T1, T2, 1.0, T3, T4, 1.0, w.tpart, gb, 1, s));
+  }
+  // W-bar from the ph B operands
+  {
+    const int waa[4] = {0, 2, 3, 1};   // W_aa[j,p,s,l] <- R[j,l,p,s]
+    const int wab[4] = {0, 2, 1, 3};   // W_ab[j,p,l,s] <- R[j,l,p,s]
+    HIP_TRY(ctx, permute(GEMM_F64, natref(Wbaa), false, Rpb, waa, 1.0, Rmb, waa, 1.0, 0));
+    HIP_TRY(ctx, permute(GEMM_F64, natref(Wbab), false, Rmb, wab, 1.0, Rpb, wab, -1.0, 0));
+    HIP_TRY(ctx, permute(GEMM_F64, natref(Wbab), false, R3b, waa, 1.0, nullptr, ID, 0.0, 1));
+  }
+  // t = W A^T:  W-bar[j,(prs)] += sum_k t-bar[j,k] A[k,(prs)];  A-bar[k,(prs)] += sum_j t-bar[j,k] W[j,(prs)]
+  HIP_TRY(ctx, mode(w.Aaa, nullptr, 0.0, tb, 0, 1, r3, 1.0, Wbaa, 1, 0, 0, r3, 1, 1, 1));
+  HIP_TRY(ctx, mode(w.Aab, nullptr, 0.0, tb, 0, 1, r3, 2.0, Wbab, 1, 0, 0, r3, 1, 1, 1));
+  HIP_TRY(ctx, mode(w.Waa, nullptr, 0.0, tb, 1, 1, r3, 1.0, Abaa, 1, 0, 0, r3, 1, 1, 1));
+  HIP_TRY(ctx, mode(w.Wab, nullptr, 0.0, tb, 1, 1, r3, 2.0, Abab, 1, 0, 0, r3, 1, 1, 1));
+  // f terms
+  HIP_TRY(ctx, launch_vjp_frank(r, fb, g, Abaa, Abab, s));
+  HIP_TRY(ctx, contract({term(w.Aaa, 1, 2, 0, 3, fb, 1.0), term(w.Aab, 1, 3, 0, 2, fb, -1.0)}, gb, 1));
+  // L terms: A-bar[k,p,r,s] += sum_i g[i,r] (L+b +- L-b)[k,i,p,s]; L3: A_ab-bar[k,p,s,r] += sum_j g[j,r] L3b[k,j,p,s]
+  {
+    const int kprs_from_krps[4] = {0, 2, 1, 3};   // dst (k,p,r,s) <- T[k,r,p,s]
+    const int kpsr_from_krps[4] = {0, 2, 3, 1};   // dst (k,p,s,r) <- T[k,r,p,s]
+    HIP_TRY(ctx, mode(Lpb, Lmb, 1.0, g, 1, r, r2, 1.0, T1, 1, r3, 0, r2, 1, 1, 0));
+    HIP_TRY(ctx, permute(GEMM_F64, natref(Abaa), false, T1, kprs_from_krps, 1.0, nullptr, ID, 0.0, 1));
+    HIP_TRY(ctx, mode(Lpb, Lmb, -1.0, g, 1, r, r2, 1.0, T1, 1, r3, 0, r2, 1, 1, 0));
+    HIP_TRY(ctx, permute(GEMM_F64, natref(Abab), false, T1, kprs_from_krps, 1.0, nullptr, ID, 0.0, 1));
+    HIP_TRY(ctx, mode(L3b, nullptr, 0.0, g, 1, r, r2, 1.0, T1, 1, r3, 0, r2, 1, 1, 0));
+    HIP_TRY(ctx, permute(GEMM_F64, natref(Abab), false, T1, kpsr_from_krps, 1.0, nullptr, ID, 0.0, 1));
+    // gamma-bar[i,r] += sum L+b[k,i,p,s] (A_aa + A_ab)[k,p,r,s] + L-b (A_aa - A_ab)
+    const int i_kps[4] = {1, 0, 2, 3};   // [i][k,p,s] from L[k,i,p,s]
+    const int r_kps[4] = {2, 0, 1, 3};   // [r][k,p,s] from X[k,p,r,s]
+    HIP_TRY(ctx, permute(GEMM_F64, natref(T1), false, Lpb, i_kps, 1.0, nullptr, ID, 0.0, 0));
+    HIP_TRY(ctx, permute(GEMM_F64, natref(T2), false, w.Aaa, r_kps, 1.0, w.Aab, r_kps, 1.0, 0));
+    HIP_TRY(ctx, permute(GEMM_F64, natref(T3), false, Lmb, i_kps, 1.0, nullptr, ID, 0.0, 0));
+    HIP_TRY(ctx, permute(GEMM_F64, natref(T4), false, w.Aaa, r_kps, 1.0, w.Aab, r_kps, -1.0, 0));
+    HIP_TRY(ctx, launch_gram(r, T1, T2, 1.0, T3, T4, 1.0, w.tpart, gb, 1, s));
+    // gamma-bar[j,r] += sum L3b[k,j,p,s] A_ab[k,p,s,r]
+    const int r_kps3[4] = {3, 0, 1, 2};  // [r][k,p,s] from A_ab[k,p,s,r]
+    HIP_TRY(ctx, permute(GEMM_F64, natref(T1), false, L3b, i_kps, 1.0, nullptr, ID, 0.0, 0));
+    HIP_TRY(ctx, permute(GEMM_F64, natref(T2), false, w.Aab, r_kps3, 1.0, nullptr, ID, 0.0, 0));
+    HIP_TRY(ctx, launch_gram(r, T1, T2, 1.0, nullptr, nullptr, 0.0, w.tpart, gb, 1, s));
+  }
+  // W = Gamma2 - 2/3 g^g:  gamma-bar from W-bar
+  HIP_TRY(ctx, contract({term(Wbaa, 0, 2, 1, 3, g, -2.0 / 3.0), term(Wbaa, 1, 3, 0, 2, g, -2.0 / 3.0),
+                         term(Wbaa, 0, 3, 1, 2, g, 2.0 / 3.0), term(Wbaa, 1, 2, 0, 3, g, 2.0 / 3.0),
+                         term(Wbab, 0, 2, 1, 3, g, -2.0 / 3.0), term(Wbab, 1, 3, 0, 2, g, -2.0 / 3.0)},
+                        gb, 1));
+  // Gamma2-bar = G-bar (GEMM) + W-bar;  d2-bar = 2 Gamma2-bar (projected)
+  HIP_TRY(ctx, permute(GEMM_F64, natref(Gbaa), false, Wbaa, ID, 1.0, nullptr, ID, 0.0, 1));
+  HIP_TRY(ctx, permute(GEMM_F64, natref(Gbab), false, Wbab, ID, 1.0, nullptr, ID, 0.0, 1));
+  HIP_TRY(ctx, launch_proj(PROJ_AA, r, 2.0, Gbaa, d2aa_bar, s));
+  HIP_TRY(ctx, launch_proj(PROJ_AB, r, 2.0, Gbab, d2ab_bar, s));
+  HIP_TRY(ctx, launch_proj(PROJ_SYM2, r, 1.0, gb, d1_bar, s));
+  // fold adjoint -> V-bar, h-bar
+  HIP_TRY(ctx, launch_vjp_fold(r, N, Abaa, Abab, Vraw, hb_raw, s));
+  HIP_TRY(ctx, launch_proj(PROJ_V, r, 1.0, Vraw, V_bar, s));
+  HIP_TRY(ctx, launch_proj(PROJ_SYM2, r, 1.0, hb_raw, h_bar, s));
+  return ACSE_OK;
+}
+
+extern "C" acse_status acse_energy_vjp(acse_ctx ctx, const acse_problem *prob, double Ebar,
+                                       double *h_bar, double *V_bar, double *d2aa_bar,
+                                       double *d2ab_bar) {
+  acse_status st = validate(ctx, prob, nullptr, false);
+  if (st != ACSE_OK) return st;
+  if (!std::isfinite(Ebar)) return fail(ctx, ACSE_ERR_ARG, "Ebar is not finite");
+  for (const void *q : {static_cast<const void *>(h_bar), static_cast<const void *>(V_bar),
+                        static_cast<const void *>(d2aa_bar), static_cast<const void *>(d2ab_bar)})
+    if ((st = check_out(ctx, q, "VJP array")) != ACSE_OK) return st;
+  HIP_TRY(ctx, hipSetDevice(ctx->device));
+  if ((st = ensure_vjp_ws(ctx)) != ACSE_OK) return st;
+  const int r = prob->r;
+  const int N = prob->n_alpha + prob->n_beta;
+  const int64_t r2 = (int64_t)r * r;
+  Workspace &w = ctx->ws;
+  hipStream_t s = ctx->stream;
+  double *zero = ctx->vnat[0], *D = ctx->vnat[1], *Vraw = ctx->vnat[2];
+  double *hb_raw = ctx->vsmall + 4 * r2;
+  // E = 2 <K_s, d2aa + d2ab> with K_s = 2 A_ab of the fold:
+  //   d2-bar = 2 Ebar K_s (projected);  through the fold, K_s-bar = 2 Ebar (d2aa + d2ab)
+  HIP_TRY(ctx, launch_fold(r, N, prob->h, prob->V, w.Aaa, w.Aab, s));
+  HIP_TRY(ctx, launch_proj(PROJ_AA, r, 4.0 * Ebar, w.Aab, d2aa_bar, s));
+  HIP_TRY(ctx, launch_proj(PROJ_AB, r, 4.0 * Ebar, w.Aab, d2ab_bar, s));
+  PermArgs a{};
+  a.r = r; a.rows = r2; a.ld = r2;
+  a.src1 = prob->d2aa; a.s1[0] = r2 * r; a.s1[1] = r2; a.s1[2] = r; a.s1[3] = 1; a.c1 = 4.0 * Ebar;
+  a.src2 = prob->d2ab; a.s2[0] = r2 * r; a.s2[1] = r2; a.s2[2] = r; a.s2[3] = 1; a.c2 = 4.0 * Ebar;
+  HIP_TRY(ctx, launch_permute4(GEMM_F64, a, OperandRef{D, nullptr}, s));
+  HIP_TRY(ctx, launch_fill(r2 * r2, 0.0, zero, s));
+  HIP_TRY(ctx, launch_vjp_fold(r, N, zero, D, Vraw, hb_raw, s));
+  HIP_TRY(ctx, launch_proj(PROJ_V, r, 1.0, Vraw, V_bar, s));
+  HIP_TRY(ctx, launch_proj(PROJ_SYM2, r, 1.0, hb_raw, h_bar, s));
+  return ACSE_OK;
+}

@@ -22,6 +22,7 @@ struct ModeArgs {
   double alpha;
   int64_t adiv, so1, so0, sx, sb;
   int out_cols_fast;  // output contiguous along (a,b) columns rather than along x
+  int accumulate;     // FP64 output only: out += result
 };
 constexpr int kModeMaxR = 96;
 size_t mode_lds_bytes(int r);
@@ -51,7 +52,12 @@ hipError_t launch_finish(int r, double sigma, const double *Saa, const double *S
                          const ActiveBits &active, double *Maa, double *Mab, double *partial,
                          double *sum_out, hipStream_t s);
 int64_t finish_partials(int r);
-hipError_t launch_t_reduce(int r, int nparts, const double *part, double *t, hipStream_t s);
+hipError_t launch_t_reduce(int r, int nparts, const double *part, double *t, hipStream_t s,
+                           int accumulate = 0);
+// out[x,y] (+)= sum_z (w1 P1[x,z] Q1[y,z] + w2 P2[x,z] Q2[y,z]),  z in [0, r^3), P*,Q* natural [r][r^3]
+hipError_t launch_gram(int r, const double *P1, const double *Q1, double w1, const double *P2,
+                       const double *Q2, double w2, double *part, double *out, int accumulate,
+                       hipStream_t s);
 int t_partial_blocks();
 // t[j,k] = sum_{prs} (W_aa[j,p,r,s] A_aa[k,p,r,s] + 2 W_ab[j,p,r,s] A_ab[k,p,r,s])
 hipError_t launch_t(int r, const double *Waa, const double *Aaa, const double *Wab,

@@ -20,6 +20,10 @@ struct OutF64 {
   double *p;
   __device__ void put(int64_t i, double v) const { p[i] = v; }
 };
+struct OutF64Acc {
+  double *p;
+  __device__ void put(int64_t i, double v) const { p[i] += v; }
+};
 struct OutF32 {
   float *p;
   __device__ void put(int64_t i, double v) const { p[i] = (float)v; }
@@ -550,7 +554,7 @@ constexpr int kTBlocks = 512;
 
 __global__ void __launch_bounds__(256)
 k_t_partial(int r, const double *__restrict__ Waa, const double *__restrict__ Aaa,
-            const double *__restrict__ Wab, const double *__restrict__ Aab,
+            const double *__restrict__ Wab, const double *__restrict__ Aab, double w1, double w2,
             double *__restrict__ part) {
   extern __shared__ double t_smem[];
   const int rp = (r + 3) & ~3;      // j / k extent covered by 4 x 4 tiles
@@ -608,7 +612,7 @@ k_t_partial(int r, const double *__restrict__ Waa, const double *__restrict__ Aa
 #pragma unroll
         for (int a = 0; a < 4; ++a)
 #pragma unroll
-          for (int b = 0; b < 4; ++b) acc[u][a * 4 + b] += wa[a] * aa[b] + 2.0 * wb[a] * ab[b];
+          for (int b = 0; b < 4; ++b) acc[u][a * 4 + b] += w1 * wa[a] * aa[b] + w2 * wb[a] * ab[b];
       }
     }
     __syncthreads();
@@ -630,14 +634,14 @@ k_t_partial(int r, const double *__restrict__ Waa, const double *__restrict__ Aa
 // t[j,k] = sum over the per-block partials of k_t_partial: one wavefront per
 // output, lanes stride over the partials, then a shuffle reduction (fixed order).
 __global__ void __launch_bounds__(256)
-k_t_reduce(int r, int nparts, const double *__restrict__ part, double *__restrict__ t) {
+k_t_reduce(int r, int nparts, const double *__restrict__ part, double *__restrict__ t, int accumulate) {
   const int lane = threadIdx.x & 63;
   const int e = blockIdx.x * 4 + (threadIdx.x >> 6);
   if (e >= r * r) return;
   double acc = 0.0;
   for (int q = lane; q < nparts; q += 64) acc += part[(int64_t)q * r * r + e];
   for (int off = 32; off > 0; off >>= 1) acc += __shfl_down(acc, off, 64);
-  if (lane == 0) t[e] = acc;
+  if (lane == 0) t[e] = accumulate ? t[e] + acc : acc;
 }
 
 // ---------------------------------------------------------------------------
@@ -807,6 +811,15 @@ hipError_t launch_mode(GemmPrec prec, const ModeArgs &m, const OperandRef &out, 
   const int64_t ncols = (int64_t)m.A * m.Bn;
   const dim3 grid((unsigned)((ncols + kModeCols - 1) / kModeCols));
   const size_t lds = mode_lds_bytes(m.r);
+  if (m.accumulate) {
+    if (prec != GEMM_F64) return hipErrorInvalidValue;
+    using O = OutF64Acc;
+    hipError_t err = hipFuncSetAttribute(reinterpret_cast<const void *>(&k_mode<O>),
+                                         hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (err != hipSuccess) return err;
+    hipLaunchKernelGGL((k_mode<O>), grid, dim3(256), lds, s, m, O{static_cast<double *>(out.hi)});
+    return hipGetLastError();
+  }
   ACSE_DISPATCH_OUT(prec, {
     hipError_t err = hipFuncSetAttribute(reinterpret_cast<const void *>(&k_mode<O>),
                                          hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
@@ -855,23 +868,33 @@ int64_t finish_partials(int r) {
   return std::max<int64_t>(nt * nt, ((int64_t)r * r * r * r + 255) / 256);
 }
 
-hipError_t launch_t_reduce(int r, int nparts, const double *part, double *t, hipStream_t s) {
-  hipLaunchKernelGGL(k_t_reduce, dim3((unsigned)((r * r + 3) / 4)), dim3(256), 0, s, r, nparts, part, t);
+hipError_t launch_t_reduce(int r, int nparts, const double *part, double *t, hipStream_t s,
+                           int accumulate) {
+  hipLaunchKernelGGL(k_t_reduce, dim3((unsigned)((r * r + 3) / 4)), dim3(256), 0, s, r, nparts, part, t,
+                     accumulate);
   return hipGetLastError();
 }
 
 int t_partial_blocks() { return kTBlocks; }
 
-hipError_t launch_t(int r, const double *Waa, const double *Aaa, const double *Wab,
-                    const double *Aab, double *part, double *t, hipStream_t s) {
+hipError_t launch_gram(int r, const double *P1, const double *Q1, double w1, const double *P2,
+                       const double *Q2, double w2, double *part, double *out, int accumulate,
+                       hipStream_t s) {
   const int ls = ((r + 3) & ~3) + 2;
   const size_t lds = (size_t)4 * kTChunk * ls * sizeof(double);
   hipError_t err = hipFuncSetAttribute(reinterpret_cast<const void *>(&k_t_partial),
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   if (err != hipSuccess) return err;
-  hipLaunchKernelGGL(k_t_partial, dim3(kTBlocks), dim3(256), lds, s, r, Waa, Aaa, Wab, Aab, part);
-  return launch_t_reduce(r, kTBlocks, part, t, s);
+  if (!P2) { P2 = P1; Q2 = Q1; w2 = 0.0; }
+  hipLaunchKernelGGL(k_t_partial, dim3(kTBlocks), dim3(256), lds, s, r, P1, Q1, P2, Q2, w1, w2, part);
+  return launch_t_reduce(r, kTBlocks, part, out, s, accumulate);
 }
+
+hipError_t launch_t(int r, const double *Waa, const double *Aaa, const double *Wab,
+                    const double *Aab, double *part, double *t, hipStream_t s) {
+  return launch_gram(r, Waa, Aaa, 1.0, Wab, Aab, 2.0, part, t, 0, s);
+}
+
 
 hipError_t launch_energy(int r, int N, const double *h, const double *V, const double *d2aa,
                          const double *d2ab, double *partial, double *E_out, hipStream_t s) {

@@ -1,0 +1,47 @@
+// Launchers of the adjoint kernels (vjp.hip).
+#pragma once
+#include "tensor_ops.h"
+
+namespace acse {
+
+// dst[row][col] = c1 src1[...] + c2 src2[...], row = (a,b), col = (c,d) over r^2 x r^2,
+// source index a*s[0] + b*s[1] + c*s[2] + d*s[3]; rows x ld output (zero padding
+// unless accumulating).
+struct PermArgs {
+  int r;
+  int64_t rows, ld;
+  const double *src1;
+  int64_t s1[4];
+  double c1;
+  const double *src2;  // may be null
+  int64_t s2[4];
+  double c2;
+  int accumulate;      // FP64 output only: dst += value (padding untouched)
+};
+hipError_t launch_permute4(GemmPrec prec, const PermArgs &a, const OperandRef &out, hipStream_t s);
+
+// out[x,y] (+)= sum_t c_t sum_{u,v} T_t[x sx + y sy + u su + v sv] M_t[u*r + v]
+struct ContractTerm {
+  const double *T;
+  int64_t sx, sy, su, sv;
+  const double *M;
+  double c;
+};
+constexpr int kMaxContractTerms = 6;
+struct ContractArgs {
+  ContractTerm term[kMaxContractTerms];
+  int nterms;
+};
+hipError_t launch_contract42(int r, const ContractArgs &a, double *out, int accumulate, hipStream_t s);
+
+hipError_t launch_vjp_pe(int r, const double *Saa, const double *Sab, double *Ppb, double *Pmb,
+                         double *E3b, hipStream_t s);
+hipError_t launch_vjp_frank(int r, const double *fb, const double *g, double *Abaa, double *Abab,
+                            hipStream_t s);
+hipError_t launch_vjp_fold(int r, int N, const double *Abaa, const double *Abab, double *Vb_raw,
+                           double *hb_raw, hipStream_t s);
+enum ProjKind { PROJ_SYM2, PROJ_V, PROJ_AA, PROJ_AB };
+hipError_t launch_proj(ProjKind k, int r, double c, const double *x, double *out, hipStream_t s);
+hipError_t launch_identity(int r, double *I, hipStream_t s);
+
+}  // namespace acse

@@ -123,3 +123,30 @@ def batched_problems(seed=0, sizes=BATCH_SIZES):
             g, d2aa, d2ab = rdm_blocks(rng, r, N, occ)
             out.append(dict(r=r, N=N, h=h, V=V, gamma=g, d2aa=d2aa, d2ab=d2ab))
     return out
+
+
+def symmetric_direction(rng, r, scale=1.0):
+    """A random direction in the structured input space: h and gamma symmetric,
+    V with the 8-fold symmetry of (pq|rs), d2aa antisymmetric in each pair and
+    Hermitian, d2ab Hermitian and pair-exchange symmetric (each unit Frobenius
+    norm times ``scale``).  Used for finite-difference checks of adjoints."""
+    def sym2():
+        x = rng.normal(size=(r, r))
+        return 0.5 * (x + x.T)
+
+    x = rng.normal(size=(r, r, r, r))
+    perms = [(0, 1, 2, 3), (1, 0, 2, 3), (0, 1, 3, 2), (1, 0, 3, 2),
+             (2, 3, 0, 1), (3, 2, 0, 1), (2, 3, 1, 0), (3, 2, 1, 0)]
+    V = sum(x.transpose(p) for p in perms) / 8.0
+    x = rng.normal(size=(r, r, r, r))
+    y = x - x.transpose(1, 0, 2, 3) - x.transpose(0, 1, 3, 2) + x.transpose(1, 0, 3, 2)
+    daa = y + y.transpose(2, 3, 0, 1)
+    x = rng.normal(size=(r, r, r, r))
+    dab = x + x.transpose(2, 3, 0, 1) + x.transpose(1, 0, 3, 2) + x.transpose(3, 2, 1, 0)
+    out = dict(h=sym2(), V=V, gamma=sym2(), d2aa=daa, d2ab=dab)
+    return {k: scale * v / np.linalg.norm(v) for k, v in out.items()}
+
+
+def cotangent(rng, r):
+    """A seeded Gaussian cotangent (Rbar_aa, Rbar_ab) on the residual blocks."""
+    return rng.normal(size=(r, r, r, r)), rng.normal(size=(r, r, r, r))

@@ -1,0 +1,175 @@
+"""GPU parity of the hand-written adjoints (acse_residual_vjp, acse_energy_vjp).
+
+* FP64 against the oracle adjoint (autograd of the oracle forward, projected)
+  at r = 4 (FCI RDMs), 6, 10 and 13: relative 1e-10 per gradient.
+* r = 30, N = 20 (the differentiation workload): central finite differences
+  (step 1e-5) of the oracle's FP64 forward along one structured direction per
+  input, against <gradient, direction>, FP64 and FP32.
+* FP32 / split-BF16 contractions against the FP64 oracle adjoint, stated
+  per-gradient tolerances.
+* The torch.autograd.Function wrappers give the same gradients, and two calls
+  are bitwise identical.
+"""
+import numpy as np
+import pytest
+
+from oracle import adjoint as adj
+from oracle import fermion as fm
+from oracle import step as ost
+from synth import generators as gen
+
+pytestmark = pytest.mark.gpu
+
+KEYS = ("h", "V", "gamma", "d2aa", "d2ab")
+TOL64 = 1e-10
+# normwise relative error of each gradient against the FP64 oracle adjoint
+MIXED_TOL = {"fp32": 1e-5, "bf16x3": 5e-5}
+
+
+@pytest.fixture(scope="module")
+def acse():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.fail("no GPU visible")
+    import paper_2604_02550_amd as acse
+    return acse
+
+
+@pytest.fixture(scope="module")
+def ctx(acse):
+    return acse.Context(r_max=30)
+
+
+def rel(a, b):
+    a, b = np.asarray(a), np.asarray(b)
+    return float(np.linalg.norm((a - b).ravel()) / max(np.linalg.norm(b.ravel()), 1e-300))
+
+
+def maxrel(a, b):
+    return float(np.abs(np.asarray(a) - np.asarray(b)).max() / max(np.abs(b).max(), 1e-300))
+
+
+def cpu(t):
+    return t.detach().cpu().numpy()
+
+
+def tiny_fci(seed=0):
+    rng = np.random.default_rng(seed)
+    h, V = gen.hamiltonian(rng, 4, 6)
+    p = fm.fci_singlet_problem(h, V, 4)
+    return dict(r=4, N=4, h=h, V=V, gamma=p["gamma"], d2aa=p["d2aa"], d2ab=p["d2ab"])
+
+
+PROBLEMS = {
+    "tiny_fci": lambda: tiny_fci(0),
+    "r6": lambda: gen.problem(6, 4, 12, seed=1),
+    "r10": lambda: gen.problem(10, 6, 20, seed=2),
+    "r13": lambda: gen.problem(13, 8, 26, seed=3),
+}
+
+
+def gpu_vjp(ctx, p, Rb, precision="fp64"):
+    out = ctx.residual_vjp(p["h"], p["V"], p["gamma"], p["d2aa"], p["d2ab"], p["N"] // 2,
+                           Rb[0], Rb[1], precision=precision)
+    return dict(zip(KEYS, [cpu(x) for x in out]))
+
+
+@pytest.mark.parametrize("name", list(PROBLEMS))
+def test_residual_vjp_fp64_vs_oracle(ctx, name):
+    p = PROBLEMS[name]()
+    print(f"[residual_vjp_fp64] {name} r={p['r']}", flush=True)
+    Rb = gen.cotangent(np.random.default_rng(21), p["r"])
+    ref = adj.residual_vjp(p["h"], p["V"], p["N"], p["gamma"], p["d2aa"], p["d2ab"], *Rb)
+    got = gpu_vjp(ctx, p, Rb)
+    for k in KEYS:
+        assert rel(got[k], ref[k]) < TOL64, (k, rel(got[k], ref[k]))
+        assert maxrel(got[k], ref[k]) < TOL64, (k, maxrel(got[k], ref[k]))
+
+
+@pytest.mark.parametrize("name", list(PROBLEMS))
+def test_energy_vjp_fp64_vs_oracle(ctx, name):
+    p = PROBLEMS[name]()
+    ref = adj.energy_vjp(p["h"], p["V"], p["N"], p["d2aa"], p["d2ab"], Ebar=-1.3)
+    got = ctx.energy_vjp(p["h"], p["V"], p["d2aa"], p["d2ab"], p["N"] // 2, Ebar=-1.3)
+    for k, x in zip(("h", "V", "d2aa", "d2ab"), got):
+        assert rel(cpu(x), ref[k]) < TOL64 and maxrel(cpu(x), ref[k]) < TOL64, k
+
+
+@pytest.mark.parametrize("precision", ["fp32", "bf16x3"])
+def test_residual_vjp_mixed_vs_oracle(ctx, precision):
+    p = PROBLEMS["r13"]()
+    Rb = gen.cotangent(np.random.default_rng(22), p["r"])
+    ref = adj.residual_vjp(p["h"], p["V"], p["N"], p["gamma"], p["d2aa"], p["d2ab"], *Rb)
+    got = gpu_vjp(ctx, p, Rb, precision)
+    for k in KEYS:
+        e = rel(got[k], ref[k])
+        print(f"[vjp {precision}] {k} rel {e:.2e}", flush=True)
+        assert e < MIXED_TOL[precision], (k, e)
+
+
+def oracle_loss(p, Rb, **over):
+    q = {k: over.get(k, p[k]) for k in KEYS}
+    raa, rab, _ = ost.residual(q["h"], q["V"], p["N"], q["gamma"], q["d2aa"], q["d2ab"])
+    return float(np.sum(Rb[0] * raa) + np.sum(Rb[1] * rab))
+
+
+@pytest.fixture(scope="module")
+def vjp30():
+    p = gen.named("vjp30")
+    rng = np.random.default_rng(23)
+    Rb = gen.cotangent(rng, p["r"])
+    dirs = gen.symmetric_direction(rng, p["r"])
+    t = 1e-5
+    fd = {}
+    for k in KEYS:
+        print(f"[vjp30 fd] {k}", flush=True)
+        fd[k] = (oracle_loss(p, Rb, **{k: p[k] + t * dirs[k]})
+                 - oracle_loss(p, Rb, **{k: p[k] - t * dirs[k]})) / (2 * t)
+    return p, Rb, dirs, fd
+
+
+@pytest.mark.parametrize("precision,tol", [("fp64", 1e-7), ("fp32", 1e-4)])
+def test_residual_vjp_r30_finite_difference(ctx, vjp30, precision, tol):
+    p, Rb, dirs, fd = vjp30
+    got = gpu_vjp(ctx, p, Rb, precision)
+    for k in KEYS:
+        an = float(np.sum(got[k] * dirs[k]))
+        scale = max(abs(fd[k]), np.linalg.norm(got[k]))
+        print(f"[vjp30 {precision}] {k} fd {fd[k]:.10e} an {an:.10e}", flush=True)
+        assert abs(an - fd[k]) <= tol * scale, (k, an, fd[k])
+
+
+def test_autograd_function_and_determinism(acse, ctx):
+    import torch
+    p = PROBLEMS["r10"]()
+    dev = ctx.device
+    x = [torch.tensor(p[k], device=dev, requires_grad=True) for k in KEYS]
+    Rb = [torch.tensor(a, device=dev) for a in gen.cotangent(np.random.default_rng(24), p["r"])]
+    Raa, Rab = acse.ACSEResidual.apply(ctx, *x, p["N"] // 2, "fp64")
+    L = (Rb[0] * Raa).sum() + (Rb[1] * Rab).sum()
+    L.backward()
+    direct = ctx.residual_vjp(*[t.detach() for t in x], p["N"] // 2, Rb[0], Rb[1])
+    again = ctx.residual_vjp(*[t.detach() for t in x], p["N"] // 2, Rb[0], Rb[1])
+    for t, a, b in zip(x, direct, again):
+        assert torch.equal(t.grad, a)
+        assert torch.equal(a, b)
+    # energy through its Function
+    y = [torch.tensor(p[k], device=dev, requires_grad=True) for k in ("h", "V", "d2aa", "d2ab")]
+    E = acse.ACSEEnergy.apply(ctx, *y, p["N"] // 2)
+    assert abs(E.item() - ost.energy(p["h"], p["V"], p["N"], p["d2aa"], p["d2ab"])) < 1e-10 * abs(E.item())
+    (2.0 * E).backward()
+    ref = adj.energy_vjp(p["h"], p["V"], p["N"], p["d2aa"], p["d2ab"], Ebar=2.0)
+    for t, k in zip(y, ("h", "V", "d2aa", "d2ab")):
+        assert rel(cpu(t.grad), ref[k]) < TOL64, k
+
+
+def test_vjp_argument_errors(acse, ctx):
+    import torch
+    p = PROBLEMS["r6"]()
+    prob, keep = ctx.problem(p["h"], p["V"], p["gamma"], p["d2aa"], p["d2ab"], p["N"] // 2)
+    opts = ctx.options("fp64")
+    out = [torch.empty_like(t) for t in keep]
+    with pytest.raises(acse.AcseError):
+        ctx.residual_vjp_raw(prob, opts, None, keep[3], *out)
+    with pytest.raises(acse.AcseError):
+        ctx.energy_vjp_raw(prob, float("nan"), out[0], out[1], out[3], out[4])
