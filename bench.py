@@ -48,6 +48,8 @@ def parse():
     ap.add_argument("--modes", default="fp64,fp32,bf16x3")
     ap.add_argument("--eps", type=float, default=1e-3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--batched-modes", default="fp64,fp32",
+                    help="precisions of the batched-instances measurement ('' to skip)")
     ap.add_argument("--calibrate-copy-mib", type=int, default=0,
                     help="run one plain device copy of this many MiB (counter calibration)")
     return ap.parse_args()
@@ -63,6 +65,66 @@ TRAITS = {"fp64": "TrF64", "fp32": "TrF32", "bf16x3": "TrBF16x3"}
 def gemm_kernel_name(prec, cfg):
     bm, bn, bk = TILE_SHAPES[prec][cfg]
     return f"acse::gemm_nt_kernel<acse::{TRAITS[prec]}, {bm}, {bn}, {bk}>"
+
+
+def bench_batched(acse, ctx, gen, torch, modes, steps, warmup):
+    """Twelve instances (r in {20, 28, 36, 44}, ground + 2 excited states each):
+    one acse_residual_batched call per step against twelve acse_residual calls
+    (each with its own autotuned tile configuration)."""
+    dev = torch.device("cuda", 0)
+    batch = gen.batched_problems(seed=0)
+    probs, keep, outs = [], [], []
+    for p in batch:
+        prob, t = ctx.problem(p["h"], p["V"], p["gamma"], p["d2aa"], p["d2ab"], p["N"] // 2)
+        probs.append(prob)
+        keep.append(t)
+        r = p["r"]
+        outs.append([torch.empty((r, r, r, r), dtype=torch.float64, device=dev) for _ in range(2)])
+    Ra, Rb = [o[0] for o in outs], [o[1] for o in outs]
+    flops = sum(10 * p["r"] ** 6 for p in batch)
+    res = {}
+    for mode in modes:
+        opts = acse.Context.options(mode)
+        best, tile_ms = ctx.autotune_batched_raw(probs, opts)
+        for prob in probs:
+            ctx.autotune_raw(prob, opts)
+
+        def timed(fn):
+            for _ in range(warmup):
+                fn()
+            torch.cuda.synchronize()
+            a = torch.cuda.Event(enable_timing=True)
+            b = torch.cuda.Event(enable_timing=True)
+            a.record(ctx.stream)
+            for _ in range(steps):
+                fn()
+            b.record(ctx.stream)
+            torch.cuda.synchronize()
+            return a.elapsed_time(b) / steps
+
+        def batched():
+            ctx.residual_batched_raw(probs, opts, Ra, Rb, want_norm=False)
+
+        def sequential():
+            for prob, o in zip(probs, outs):
+                ctx.residual_raw(prob, opts, o[0], o[1], want_norm=False)
+
+        ms_b = timed(batched)
+        ms_s = timed(sequential)
+        ctx.profile(True)
+        batched()
+        prof = ctx.profile_read()
+        ctx.profile(False)
+        gemm_ms = prof["gemm"][0]
+        res[mode] = dict(instances=len(batch), sizes=sorted({p["r"] for p in batch}),
+                         batched_ms=ms_b, sequential_ms=ms_s,
+                         batched_evals_per_s=len(batch) * 1e3 / ms_b,
+                         sequential_evals_per_s=len(batch) * 1e3 / ms_s,
+                         speedup=ms_s / ms_b, tile_config=best, tile_gemm_ms=tile_ms,
+                         persistent_gemm_ms=gemm_ms,
+                         persistent_gemm_tflops=flops / (gemm_ms * 1e-3) / 1e12,
+                         useful_tflops=flops / (ms_b * 1e-3) / 1e12)
+    return res
 
 
 def src_hash():
@@ -213,6 +275,9 @@ def main():
         "residual_only_evals_per_s": hr["residual_evals_per_s"],
         "modes": results,
     }
+    if args.batched_modes:
+        line["batched_instances"] = bench_batched(acse, ctx, gen, torch, args.batched_modes.split(","),
+                                                  args.steps, args.warmup)
     if not args.no_cpu_baseline:
         import torch as _t
         from oracle import step as ost

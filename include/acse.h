@@ -182,6 +182,33 @@ acse_status acse_profile_read(acse_ctx ctx, acse_profile_data *out);
 acse_status acse_autotune(acse_ctx ctx, const acse_problem *prob, const acse_options *opts,
                           int32_t *best_tile, double *times_ms);
 
+/* Batched residual of Eq. (4) over `count` independent instances (1 <= count
+ * <= 4096) of possibly different r, each r <= r_max: ground and excited
+ * states, several molecules.  Per instance, the RDM operands, the fold and
+ * the transforms run as in acse_residual.  The five pair-index products of
+ * all instances then run in one persistent launch: a grid sized to the
+ * resident capacity walks one tile list ordered by decreasing K.  The
+ * per-instance assembly follows.
+ *   probs       host array [count]
+ *   R_aa, R_ab  host arrays [count] of device pointers, [r_i^4] each
+ *   norm2_host  host [count] (||R_i||^2 as in acse_residual) or NULL;
+ *               if not NULL the call synchronises
+ *   opts        apply to every instance.  tile = -1 takes the configuration
+ *               acse_autotune_batched chose for this (precision, list of r),
+ *               else the size default.
+ * The first call (and any call that needs more room) allocates a batch
+ * workspace kept until acse_destroy.  Errors are as for acse_residual; the
+ * detail names the failing instance. */
+acse_status acse_residual_batched(acse_ctx ctx, int32_t count, const acse_problem *probs,
+                                  const acse_options *opts, double *const *R_aa,
+                                  double *const *R_ab, double *norm2_host);
+
+/* Autotuner of the batched launch: times the persistent product launch of this
+ * batch under every tile configuration and caches the fastest for
+ * (precision, list of r).  Outputs as for acse_autotune.  Synchronises. */
+acse_status acse_autotune_batched(acse_ctx ctx, int32_t count, const acse_problem *probs,
+                                  const acse_options *opts, int32_t *best_tile, double *times_ms);
+
 /* Human-readable name of a status code (static storage). */
 const char *acse_status_str(acse_status s);
 

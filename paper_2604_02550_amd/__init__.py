@@ -32,7 +32,8 @@ STATUS = {0: "ACSE_OK", 1: "ACSE_ERR_ARG", 2: "ACSE_ERR_SHAPE", 3: "ACSE_ERR_ALI
 EXPORTS = ("acse_create", "acse_destroy", "acse_set_stream", "acse_residual", "acse_update_map",
            "acse_energy", "acse_step", "acse_status_str", "acse_last_error",
            "acse_workspace_bytes", "acse_profile_enable", "acse_profile_read", "acse_autotune",
-           "acse_residual_vjp", "acse_energy_vjp")
+           "acse_residual_vjp", "acse_energy_vjp", "acse_residual_batched",
+           "acse_autotune_batched")
 NUM_TILE_CONFIGS = 3
 NUM_STAGES = 6
 STAGES = ("rdm_operands", "fold", "transforms", "gemm", "assembly", "step_tail")
@@ -75,6 +76,12 @@ _sig = {
                                          _P, _P, _P, _P, _P, _P, _P]),
     "acse_energy_vjp": (ctypes.c_int, [_P, ctypes.POINTER(Problem), ctypes.c_double,
                                        _P, _P, _P, _P]),
+    "acse_residual_batched": (ctypes.c_int, [_P, ctypes.c_int32, ctypes.POINTER(Problem),
+                                             ctypes.POINTER(Options), ctypes.POINTER(ctypes.c_void_p),
+                                             ctypes.POINTER(ctypes.c_void_p), _D]),
+    "acse_autotune_batched": (ctypes.c_int, [_P, ctypes.c_int32, ctypes.POINTER(Problem),
+                                             ctypes.POINTER(Options), ctypes.POINTER(ctypes.c_int32),
+                                             _D]),
 }
 for _name, (_res, _args) in _sig.items():
     _fn = getattr(_lib, _name)
@@ -245,6 +252,42 @@ class Context:
         out = [torch.empty_like(x) for x in keep]
         self.residual_vjp_raw(prob, self.options(precision, None, tile), *rb, *out)
         return tuple(out)
+
+    def residual_batched_raw(self, probs, opts, R_aa, R_ab, want_norm=True):
+        """probs: sequence of Problem; R_aa/R_ab: sequences of device tensors.
+        Returns the list of ||R_i||^2 (or None)."""
+        n = len(probs)
+        parr = (Problem * n)(*probs)
+        ra = (ctypes.c_void_p * n)(*[t.data_ptr() for t in R_aa])
+        rb = (ctypes.c_void_p * n)(*[t.data_ptr() for t in R_ab])
+        n2 = (ctypes.c_double * n)()
+        self._check(_lib.acse_residual_batched(self._h, n, parr, ctypes.byref(opts), ra, rb,
+                                               n2 if want_norm else None))
+        return list(n2) if want_norm else None
+
+    def autotune_batched_raw(self, probs, opts):
+        n = len(probs)
+        parr = (Problem * n)(*probs)
+        best = ctypes.c_int32(-1)
+        times = (ctypes.c_double * NUM_TILE_CONFIGS)()
+        self._check(_lib.acse_autotune_batched(self._h, n, parr, ctypes.byref(opts), ctypes.byref(best),
+                                               times))
+        return best.value, list(times)
+
+    def residual_batched(self, instances, precision="fp64", tile=-1):
+        """instances: sequence of dicts with h, V, gamma, d2aa, d2ab, N.  One
+        batched call; returns [(R_aa, R_ab, norm2)] in input order."""
+        probs, keep, outs = [], [], []
+        for p in instances:
+            prob, t = self.problem(p["h"], p["V"], p["gamma"], p["d2aa"], p["d2ab"], p["N"] // 2)
+            probs.append(prob)
+            keep.append(t)
+            r = prob.r
+            outs.append([torch.empty((r, r, r, r), dtype=torch.float64, device=self.device)
+                         for _ in range(2)])
+        n2 = self.residual_batched_raw(probs, self.options(precision, None, tile),
+                                       [o[0] for o in outs], [o[1] for o in outs])
+        return [(o[0], o[1], v) for o, v in zip(outs, n2)]
 
     def energy_vjp_raw(self, prob, Ebar, h_bar, V_bar, d2aa_bar, d2ab_bar):
         self._check(_lib.acse_energy_vjp(self._h, ctypes.byref(prob), float(Ebar), _ptr(h_bar),

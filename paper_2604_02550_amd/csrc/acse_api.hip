@@ -15,6 +15,7 @@
 //   F = S - S^T (Hermitian X),  F = S + S^T (anti-Hermitian X)
 //
 // The five GEMMs (10 r^6 flops) run as one grouped MFMA launch.
+#include <algorithm>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -30,6 +31,8 @@
 using namespace acse;
 
 namespace {
+
+constexpr int kNat = 26;  // natural r^4 arrays in Workspace
 
 struct Workspace {
   // natural FP64 r^4 arrays
@@ -61,6 +64,13 @@ struct acse_ctx_s {
   double ms[ACSE_NUM_STAGES] = {};
   int64_t count[ACSE_NUM_STAGES] = {};
   std::map<std::pair<int, int>, int> tuned;  // (r, precision) -> tile configuration
+  // batched residual: one workspace per instance, sized for its own r
+  void *bbase = nullptr;
+  int64_t bbytes = 0;
+  std::map<std::string, int> tuned_batch;  // "prec:r1,r2,..." -> tile configuration
+  GemmProb *hdesc = nullptr;    // pinned staging of the persistent GEMM descriptors
+  int hdesc_cap = 0;
+  hipEvent_t hdesc_done = nullptr;  // recorded after the staging copy
   // adjoint workspace (allocated by the first VJP call)
   void *vbase = nullptr;
   int64_t vbytes = 0;
@@ -71,7 +81,6 @@ struct acse_ctx_s {
 
 namespace {
 
-constexpr int kNat = 26;  // natural r^4 arrays in Workspace
 
 acse_status fail(acse_ctx c, acse_status s, const std::string &msg) {
   if (c) c->err = msg;
@@ -114,6 +123,34 @@ bool aligned16(const void *p) { return (reinterpret_cast<uintptr_t>(p) & 15u) ==
 
 int64_t op_rows(int r) { return round_up((int64_t)r * r, kRowPad); }
 int64_t op_ld(int r) { return round_up((int64_t)r * r, kKPad); }
+
+// Lays out the workspace for orbital count r from p (p == nullptr only sizes
+// it); returns the bytes used.  `full` adds the step-only arrays (masked copy,
+// update, new 2-RDM); without it they are null.
+int64_t carve(char *p, int r, bool full, Workspace &w) {
+  const int64_t r2 = (int64_t)r * r;
+  const int64_t nat = round_up(r2 * r2 * 8, 256);
+  const int64_t opb = round_up(op_rows(r) * op_ld(r) * 8, 256);
+  char *q = p;
+  auto take = [&](int64_t bytes) {
+    char *x = q;
+    q += bytes;
+    return p ? x : nullptr;
+  };
+  double **nats[kNat] = {&w.Aaa, &w.Aab, &w.Waa, &w.Wab, &w.Haa, &w.Hab, &w.G2aa, &w.G2ab, &w.T1,
+                         &w.Caa, &w.Cab, &w.Zaa, &w.Zab, &w.Pp,  &w.Pm,  &w.E3,  &w.Saa,  &w.Sab,
+                         &w.Raa, &w.Rab, &w.Maa, &w.Mab, &w.Uaa, &w.Uab, &w.Naa, &w.Nab};
+  const int nnat = full ? kNat : kNat - 6;
+  for (int k = 0; k < kNat; ++k) *nats[k] = k < nnat ? reinterpret_cast<double *>(take(nat)) : nullptr;
+  for (int k = 0; k < 10; ++k) w.op[k] = take(opb);
+  w.fpart = reinterpret_cast<double *>(take(round_up((int64_t)r * r2 * 8, 256)));
+  w.f = reinterpret_cast<double *>(take(round_up(r2 * 8, 256)));
+  w.tpart = reinterpret_cast<double *>(take(round_up((int64_t)t_partial_blocks() * r2 * 8, 256)));
+  w.t = reinterpret_cast<double *>(take(round_up(r2 * 8, 256)));
+  w.partial = reinterpret_cast<double *>(take(round_up(finish_partials(r) * 8, 256)));
+  w.scal = reinterpret_cast<double *>(take(256));
+  return q - p;
+}
 
 OperandRef operand(const Workspace &w, int idx, GemmPrec prec, int r) {
   OperandRef o{w.op[idx], nullptr};
@@ -160,10 +197,13 @@ GemmPrec prec_of(const acse_options *o) {
 
 // Operands that depend only on (gamma, 2D): W natural, the ph B operands and
 // the pp A operands.
+acse_status prep_rdm_operands(acse_ctx c, const acse_problem *p, GemmPrec prec, Workspace &w);
 acse_status prep_rdm_operands(acse_ctx c, const acse_problem *p, GemmPrec prec) {
+  return prep_rdm_operands(c, p, prec, c->ws);
+}
+acse_status prep_rdm_operands(acse_ctx c, const acse_problem *p, GemmPrec prec, Workspace &w) {
   const int r = p->r;
   const int ld = (int)op_ld(r);
-  Workspace &w = c->ws;
   StageTimer timer(c, 0);
   HIP_TRY(c, launch_w_natural(r, p->d1, p->d2aa, p->d2ab, w.Waa, w.Wab, c->stream));
   HIP_TRY(c, launch_w_ph(prec, r, ld, p->d1, p->d2aa, p->d2ab, operand(w, OP_RP, prec, r),
@@ -184,19 +224,14 @@ ModeArgs mode_base(int r, const double *g) {
   return m;
 }
 
-// F(X) into (Oaa, Oab); sigma = -1 for Hermitian X, +1 for anti-Hermitian X.
-// If Maa is not null it receives the active-masked copy.  The norm
-// 2||O_aa||^2 + 4||O_ab||^2 lands in ws.scal[slot].
-acse_status run_map(acse_ctx c, const acse_problem *p, GemmPrec prec, int cfg, const double *Xaa,
-                    const double *Xab, double sigma, double *Oaa, double *Oab,
-                    const ActiveBits &act, double *Maa, double *Mab, int slot) {
+// Stage 2 of F(X): the O(r^4)/O(r^5) transforms that feed the products.
+acse_status map_front(acse_ctx c, const acse_problem *p, GemmPrec prec, const double *Xaa,
+                      const double *Xab, Workspace &w) {
   const int r = p->r;
   const int64_t r2 = (int64_t)r * r, r3 = r2 * r;
   const int ld = (int)op_ld(r);
   const double *g = p->d1;
-  Workspace &w = c->ws;
   hipStream_t s = c->stream;
-
   {
     StageTimer t2(c, 2);
     HIP_TRY(c, launch_f(r, Xaa, Xab, g, w.fpart, w.f, s));
@@ -238,12 +273,17 @@ acse_status run_map(acse_ctx c, const acse_problem *p, GemmPrec prec, int cfg, c
       HIP_TRY(c, launch_mode(prec, m, operand(w, OP_L3, prec, r), s));
     }
   }
-  // grouped GEMM: 2 pp + 3 ph products
-  GemmBatch batch{};
-  batch.count = 5;
+  return ACSE_OK;
+}
+
+// The five pair-index products of F(X) (2 pp + 3 ph) as GEMM descriptors.
+void map_probs(const Workspace &w, GemmPrec prec, int r, GemmProb *out) {
+  const int64_t r2 = (int64_t)r * r, r3 = r2 * r;
+  const int ld = (int)op_ld(r);
   auto set = [&](int q, int ia, int ib, double alpha, double *C, int64_t sm1, int64_t sm0,
                  int64_t sn1, int64_t sn0) {
-    GemmProb &P = batch.p[q];
+    GemmProb &P = out[q];
+    P = GemmProb{};
     OperandRef a = operand(w, ia, prec, r), bb = operand(w, ib, prec, r);
     P.A = a.hi; P.A2 = a.lo; P.B = bb.hi; P.B2 = bb.lo;
     P.C = C; P.alpha = alpha;
@@ -256,6 +296,36 @@ acse_status run_map(acse_ctx c, const acse_problem *p, GemmPrec prec, int cfg, c
   set(2, OP_LP, OP_RP, 1.0, w.Pp, r, r3, r2, 1);      // rows (k,i), cols (j,l) -> [i,j,k,l]
   set(3, OP_LM, OP_RM, 1.0, w.Pm, r, r3, r2, 1);
   set(4, OP_L3, OP_R3, -2.0, w.E3, r, r2, r3, 1);     // rows (k,j), cols (i,l) -> [i,j,k,l]
+}
+
+// Stage 4 of F(X): assembly, (ij) <-> (kl) exchange, mask and the FP64 norm
+// 2||O_aa||^2 + 4||O_ab||^2 into norm_out (device).
+acse_status map_back(acse_ctx c, const acse_problem *p, double sigma, double *Oaa, double *Oab,
+                     const ActiveBits &act, double *Maa, double *Mab, double *norm_out,
+                     Workspace &w) {
+  const int r = p->r;
+  hipStream_t s = c->stream;
+  StageTimer t4(c, 4);
+  HIP_TRY(c, launch_assemble(r, p->d1, w.t, w.Zaa, w.Zab, w.Pp, w.Pm, w.E3, w.Saa, w.Sab, s));
+  HIP_TRY(c, launch_finish(r, sigma, w.Saa, w.Sab, w.Caa, w.Cab, Oaa, Oab, act, Maa, Mab,
+                           w.partial, norm_out, s));
+  return ACSE_OK;
+}
+
+// F(X) into (Oaa, Oab); sigma = -1 for Hermitian X, +1 for anti-Hermitian X.
+// If Maa is not null it receives the active-masked copy.  The norm
+// 2||O_aa||^2 + 4||O_ab||^2 lands in ws.scal[slot].
+acse_status run_map(acse_ctx c, const acse_problem *p, GemmPrec prec, int cfg, const double *Xaa,
+                    const double *Xab, double sigma, double *Oaa, double *Oab,
+                    const ActiveBits &act, double *Maa, double *Mab, int slot) {
+  const int r = p->r;
+  const int64_t r2 = (int64_t)r * r;
+  Workspace &w = c->ws;
+  acse_status st = map_front(c, p, prec, Xaa, Xab, w);
+  if (st != ACSE_OK) return st;
+  GemmBatch batch{};
+  batch.count = 5;
+  map_probs(w, prec, r, batch.p);
   int use_cfg = cfg;
   if (use_cfg < 0) {
     auto it = c->tuned.find({r, (int)prec});
@@ -263,13 +333,9 @@ acse_status run_map(acse_ctx c, const acse_problem *p, GemmPrec prec, int cfg, c
   }
   {
     StageTimer t3(c, 3);
-    HIP_TRY(c, gemm_launch(prec, use_cfg, batch, s));
+    HIP_TRY(c, gemm_launch(prec, use_cfg, batch, c->stream));
   }
-  StageTimer t4(c, 4);
-  HIP_TRY(c, launch_assemble(r, g, w.t, w.Zaa, w.Zab, w.Pp, w.Pm, w.E3, w.Saa, w.Sab, s));
-  HIP_TRY(c, launch_finish(r, sigma, w.Saa, w.Sab, w.Caa, w.Cab, Oaa, Oab, act, Maa, Mab,
-                           w.partial, w.scal + slot, s));
-  return ACSE_OK;
+  return map_back(c, p, sigma, Oaa, Oab, act, Maa, Mab, w.scal + slot, w);
 }
 
 ActiveBits make_bits(const acse_options *o, int r, bool *any) {
@@ -330,33 +396,16 @@ acse_status acse_create(acse_ctx *out, int device, void *hip_stream, int32_t r_m
   c->stream = static_cast<hipStream_t>(hip_stream);
   c->r_max = r_max;
   if (hipSetDevice(device) != hipSuccess) { delete c; return ACSE_ERR_HIP; }
-  const int64_t n4 = (int64_t)r_max * r_max * r_max * r_max;
-  const int64_t r2 = (int64_t)r_max * r_max;
-  const int64_t nat = round_up(n4 * 8, 256);
-  const int64_t opb = round_up(op_rows(r_max) * op_ld(r_max) * 8, 256);
-  const int64_t small = round_up((int64_t)r_max * r2 * 8, 256) + round_up(r2 * 8, 256) +
-                        round_up((int64_t)t_partial_blocks() * r2 * 8, 256) + round_up(r2 * 8, 256) +
-                        round_up(finish_partials(r_max) * 8, 256) + 256;
-  c->bytes = kNat * nat + 10 * opb + small;
-  c->op_bytes = opb;
+  Workspace &w = c->ws;
+  c->bytes = carve(nullptr, r_max, true, w);
+  c->op_bytes = round_up(op_rows(r_max) * op_ld(r_max) * 8, 256);
   if (hipMalloc(&c->base, c->bytes) != hipSuccess) {
     (void)hipGetLastError();
     delete c;
     return ACSE_ERR_NOMEM;
   }
-  char *p = static_cast<char *>(c->base);
-  Workspace &w = c->ws;
-  double **nats[kNat] = {&w.Aaa, &w.Aab, &w.Waa, &w.Wab, &w.Haa, &w.Hab, &w.G2aa, &w.G2ab, &w.T1,
-                         &w.Caa, &w.Cab, &w.Zaa, &w.Zab, &w.Pp,  &w.Pm,  &w.E3,  &w.Saa,  &w.Sab,
-                         &w.Raa, &w.Rab, &w.Maa, &w.Mab, &w.Uaa, &w.Uab, &w.Naa, &w.Nab};
-  for (int q = 0; q < kNat; ++q) { *nats[q] = reinterpret_cast<double *>(p); p += nat; }
-  for (int q = 0; q < 10; ++q) { w.op[q] = p; p += opb; }
-  w.fpart = reinterpret_cast<double *>(p); p += round_up((int64_t)r_max * r2 * 8, 256);
-  w.f = reinterpret_cast<double *>(p); p += round_up(r2 * 8, 256);
-  w.tpart = reinterpret_cast<double *>(p); p += round_up((int64_t)t_partial_blocks() * r2 * 8, 256);
-  w.t = reinterpret_cast<double *>(p); p += round_up(r2 * 8, 256);
-  w.partial = reinterpret_cast<double *>(p); p += round_up(finish_partials(r_max) * 8, 256);
-  w.scal = reinterpret_cast<double *>(p);
+  carve(static_cast<char *>(c->base), r_max, true, w);
+  const int64_t opb = c->op_bytes;
   // Operand padding rows are read by full tiles: give every byte a defined value once.
   if (launch_fill((10 * opb) / 8, 0.0, reinterpret_cast<double *>(w.op[0]), c->stream) != hipSuccess ||
       hipStreamSynchronize(c->stream) != hipSuccess) {
@@ -401,6 +450,9 @@ acse_status acse_destroy(acse_ctx ctx) {
   for (auto &q : ctx->recs) { (void)hipEventDestroy(q.a); (void)hipEventDestroy(q.b); }
   for (auto e : ctx->pool) (void)hipEventDestroy(e);
   if (ctx->vbase) (void)hipFree(ctx->vbase);
+  if (ctx->bbase) (void)hipFree(ctx->bbase);
+  if (ctx->hdesc) (void)hipHostFree(ctx->hdesc);
+  if (ctx->hdesc_done) (void)hipEventDestroy(ctx->hdesc_done);
   (void)hipFree(ctx->base);
   delete ctx;
   return ACSE_OK;
@@ -932,5 +984,202 @@ extern "C" acse_status acse_energy_vjp(acse_ctx ctx, const acse_problem *prob, d
   HIP_TRY(ctx, launch_vjp_fold(r, N, zero, D, Vraw, hb_raw, s));
   HIP_TRY(ctx, launch_proj(PROJ_V, r, 1.0, Vraw, V_bar, s));
   HIP_TRY(ctx, launch_proj(PROJ_SYM2, r, 1.0, hb_raw, h_bar, s));
+  return ACSE_OK;
+}
+
+// ===========================================================================
+// Batched residual: instances of uneven r (ground and excited states, several
+// molecules) share one persistent launch of all their pair-index products.
+// ===========================================================================
+namespace {
+
+constexpr int kMaxBatch = 4096;
+
+struct BatchPlan {
+  std::vector<Workspace> ws;
+  double *norms = nullptr;
+  GemmProb *dprobs = nullptr;
+};
+
+std::string batch_key(GemmPrec prec, int count, const acse_problem *probs) {
+  std::string k = std::to_string((int)prec) + ":";
+  for (int i = 0; i < count; ++i) k += std::to_string(probs[i].r) + ",";
+  return k;
+}
+
+acse_status validate_batch(acse_ctx c, int32_t count, const acse_problem *probs,
+                           const acse_options *opts) {
+  if (!c) return ACSE_ERR_ARG;
+  if (count < 1 || count > kMaxBatch)
+    return fail(c, ACSE_ERR_ARG, "count must be in [1, " + std::to_string(kMaxBatch) + "]");
+  if (!probs) return fail(c, ACSE_ERR_ARG, "problems array is NULL");
+  for (int i = 0; i < count; ++i) {
+    acse_status st = validate(c, &probs[i], opts);
+    if (st != ACSE_OK) return fail(c, st, "instance " + std::to_string(i) + ": " + c->err);
+  }
+  return ACSE_OK;
+}
+
+acse_status ensure_batch(acse_ctx c, int count, const acse_problem *probs, BatchPlan &plan) {
+  int64_t need = 0;
+  std::vector<int64_t> off(count);
+  for (int i = 0; i < count; ++i) {
+    Workspace tmp{};
+    off[i] = need;
+    need += round_up(carve(nullptr, probs[i].r, false, tmp), 256);
+  }
+  const int64_t norms_off = need;
+  need += round_up((int64_t)count * 8, 256);
+  const int64_t probs_off = need;
+  need += round_up((int64_t)count * 5 * (int64_t)sizeof(GemmProb), 256);
+  if (need > c->bbytes) {
+    if (c->bbase) {
+      HIP_TRY(c, hipStreamSynchronize(c->stream));
+      (void)hipFree(c->bbase);
+      c->bbase = nullptr;
+      c->bbytes = 0;
+    }
+    if (hipMalloc(&c->bbase, need) != hipSuccess) {
+      (void)hipGetLastError();
+      c->bbase = nullptr;
+      return fail(c, ACSE_ERR_NOMEM, "batch workspace allocation failed");
+    }
+    c->bbytes = need;
+    HIP_TRY(c, launch_fill(need / 8, 0.0, static_cast<double *>(c->bbase), c->stream));
+  }
+  if (5 * count > c->hdesc_cap) {
+    if (c->hdesc) {
+      if (c->hdesc_done) HIP_TRY(c, hipEventSynchronize(c->hdesc_done));
+      (void)hipHostFree(c->hdesc);
+      c->hdesc = nullptr;
+      c->hdesc_cap = 0;
+    }
+    HIP_TRY(c, hipHostMalloc(reinterpret_cast<void **>(&c->hdesc), 5 * count * sizeof(GemmProb),
+                             hipHostMallocDefault));
+    c->hdesc_cap = 5 * count;
+  }
+  if (!c->hdesc_done) HIP_TRY(c, hipEventCreateWithFlags(&c->hdesc_done, hipEventDisableTiming));
+  char *base = static_cast<char *>(c->bbase);
+  plan.ws.assign(count, Workspace{});
+  for (int i = 0; i < count; ++i) carve(base + off[i], probs[i].r, false, plan.ws[i]);
+  plan.norms = reinterpret_cast<double *>(base + norms_off);
+  plan.dprobs = reinterpret_cast<GemmProb *>(base + probs_off);
+  return ACSE_OK;
+}
+
+int batch_cfg(acse_ctx c, GemmPrec prec, int count, const acse_problem *probs, int tile) {
+  if (tile >= 0) return tile;
+  auto it = c->tuned_batch.find(batch_key(prec, count, probs));
+  if (it != c->tuned_batch.end()) return it->second;
+  int64_t rmax = 0;
+  for (int i = 0; i < count; ++i) rmax = std::max<int64_t>(rmax, probs[i].r);
+  return gemm_default_cfg(prec, (int)(rmax * rmax), (int)(rmax * rmax));
+}
+
+acse_status run_batched(acse_ctx c, int count, const acse_problem *probs, GemmPrec prec, int cfg,
+                        double *const *Raa, double *const *Rab, BatchPlan &plan) {
+  acse_status st;
+  std::vector<GemmProb> gp(5 * (size_t)count);
+  for (int i = 0; i < count; ++i) {
+    const acse_problem *p = &probs[i];
+    Workspace &w = plan.ws[i];
+    if ((st = prep_rdm_operands(c, p, prec, w)) != ACSE_OK) return st;
+    {
+      StageTimer t1(c, 1);
+      HIP_TRY(c, launch_fold(p->r, p->n_alpha + p->n_beta, p->h, p->V, w.Aaa, w.Aab, c->stream));
+    }
+    if ((st = map_front(c, p, prec, w.Aaa, w.Aab, w)) != ACSE_OK) return st;
+    map_probs(w, prec, p->r, &gp[5 * (size_t)i]);
+  }
+  {
+    // the pinned staging buffer may still feed the previous call's copy
+    HIP_TRY(c, hipEventSynchronize(c->hdesc_done));
+    StageTimer t3(c, 3);
+    HIP_TRY(c, gemm_launch_persistent(prec, cfg, gp, c->hdesc, plan.dprobs, c->stream));
+    HIP_TRY(c, hipEventRecord(c->hdesc_done, c->stream));
+  }
+  const ActiveBits none{};
+  for (int i = 0; i < count; ++i)
+    if ((st = map_back(c, &probs[i], -1.0, Raa ? Raa[i] : plan.ws[i].Raa,
+                       Rab ? Rab[i] : plan.ws[i].Rab, none, nullptr, nullptr, plan.norms + i,
+                       plan.ws[i])) != ACSE_OK)
+      return st;
+  return ACSE_OK;
+}
+
+}  // namespace
+
+extern "C" acse_status acse_residual_batched(acse_ctx ctx, int32_t count, const acse_problem *probs,
+                                             const acse_options *opts, double *const *R_aa,
+                                             double *const *R_ab, double *norm2_host) {
+  acse_status st = validate_batch(ctx, count, probs, opts);
+  if (st != ACSE_OK) return st;
+  if (!R_aa || !R_ab) return fail(ctx, ACSE_ERR_ARG, "output pointer arrays are NULL");
+  for (int i = 0; i < count; ++i) {
+    if ((st = check_out(ctx, R_aa[i], "R_aa[i]")) != ACSE_OK) return st;
+    if ((st = check_out(ctx, R_ab[i], "R_ab[i]")) != ACSE_OK) return st;
+  }
+  HIP_TRY(ctx, hipSetDevice(ctx->device));
+  const GemmPrec prec = prec_of(opts);
+  BatchPlan plan;
+  if ((st = ensure_batch(ctx, count, probs, plan)) != ACSE_OK) return st;
+  const int cfg = batch_cfg(ctx, prec, count, probs, opts ? opts->tile : -1);
+  if ((st = run_batched(ctx, count, probs, prec, cfg, R_aa, R_ab, plan)) != ACSE_OK) return st;
+  if (norm2_host) {
+    HIP_TRY(ctx, hipMemcpyAsync(norm2_host, plan.norms, count * sizeof(double), hipMemcpyDeviceToHost,
+                                ctx->stream));
+    HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
+    for (int i = 0; i < count; ++i)
+      if (!std::isfinite(norm2_host[i]))
+        return fail(ctx, ACSE_ERR_NONFINITE, "||R||^2 of instance " + std::to_string(i) + " is not finite");
+  }
+  return ACSE_OK;
+}
+
+extern "C" acse_status acse_autotune_batched(acse_ctx ctx, int32_t count, const acse_problem *probs,
+                                             const acse_options *opts, int32_t *best_tile,
+                                             double *times_ms) {
+  acse_status st = validate_batch(ctx, count, probs, opts);
+  if (st != ACSE_OK) return st;
+  if (!best_tile) return fail(ctx, ACSE_ERR_ARG, "best_tile is NULL");
+  HIP_TRY(ctx, hipSetDevice(ctx->device));
+  const GemmPrec prec = prec_of(opts);
+  BatchPlan plan;
+  if ((st = ensure_batch(ctx, count, probs, plan)) != ACSE_OK) return st;
+  const bool was = ctx->profiling;
+  auto saved = std::move(ctx->recs);
+  ctx->recs.clear();
+  double best = 1e300;
+  int arg = 0;
+  for (int cfg = 0; cfg < ACSE_NUM_TILE_CONFIGS; ++cfg) {
+    ctx->profiling = false;
+    if ((st = run_batched(ctx, count, probs, prec, cfg, nullptr, nullptr, plan)) != ACSE_OK) break;
+    ctx->profiling = true;
+    for (int rep = 0; rep < 2 && st == ACSE_OK; ++rep)
+      st = run_batched(ctx, count, probs, prec, cfg, nullptr, nullptr, plan);
+    if (st != ACSE_OK) break;
+    if (hipStreamSynchronize(ctx->stream) != hipSuccess) { st = fail(ctx, ACSE_ERR_HIP, "sync"); break; }
+    double ms = 0.0;
+    int n = 0;
+    for (auto &q : ctx->recs) {
+      if (q.stage == 3) {
+        float e = 0.0f;
+        (void)hipEventElapsedTime(&e, q.a, q.b);
+        ms += e;
+        ++n;
+      }
+      ctx->pool.push_back(q.a);
+      ctx->pool.push_back(q.b);
+    }
+    ctx->recs.clear();
+    ms = n ? ms / n : 1e300;
+    if (times_ms) times_ms[cfg] = ms;
+    if (ms < best) { best = ms; arg = cfg; }
+  }
+  ctx->profiling = was;
+  ctx->recs = std::move(saved);
+  if (st != ACSE_OK) return st;
+  ctx->tuned_batch[batch_key(prec, count, probs)] = arg;
+  *best_tile = arg;
   return ACSE_OK;
 }

@@ -1,5 +1,6 @@
 // Internal declarations shared by the HIP translation units of libacse.so.
 #pragma once
+#include <vector>
 #include <hip/hip_runtime.h>
 #include <hip/hip_bf16.h>
 #include <cstdint>
@@ -52,6 +53,12 @@ constexpr int kKPad = 64;
 
 // Fills tiles_m/tiles_n/tile_begin/total_tiles and launches.
 hipError_t gemm_launch(GemmPrec prec, int cfg, GemmBatch &batch, hipStream_t s);
+// Persistent grouped launch over any number of problems: sorts `probs` in place
+// by decreasing K, fills the tile counts, stages the descriptors through
+// `host_stage` (pinned host memory the caller keeps until the copy has run)
+// into `dprobs` (device) and launches one resident-size grid.
+hipError_t gemm_launch_persistent(GemmPrec prec, int cfg, std::vector<GemmProb> &probs,
+                                  GemmProb *host_stage, GemmProb *dprobs, hipStream_t s);
 
 inline int64_t round_up(int64_t x, int64_t m) { return (x + m - 1) / m * m; }
 

@@ -10,6 +10,9 @@
 // double-buffering (the next slab's global loads are in flight while the
 // current slab feeds the MFMAs).  LDS rows are padded so that the 16 rows a
 // half-wave reads for one MFMA operand fall in distinct banks.
+#include <algorithm>
+#include <vector>
+
 #include "acse_internal.h"
 
 namespace acse {
@@ -44,9 +47,10 @@ __device__ inline typename Tr::Acc acc_zero() {
 constexpr int kNumXcd = 8;
 constexpr int kGroupM = 8;
 
+// One BM x BN output tile (and K chunk) of problem P; `local` counts the
+// problem's tiles in grouped order (split-major).
 template <class Tr, int BM, int BN, int BK>
-__global__ void __launch_bounds__(256)
-gemm_nt_kernel(const GemmBatch batch) {
+__device__ __forceinline__ void gemm_tile(const GemmProb &P, int local) {
   using T = typename Tr::T;
   using Acc = typename Tr::Acc;
   constexpr int NT = 256;
@@ -64,20 +68,7 @@ gemm_nt_kernel(const GemmBatch batch) {
   __shared__ __attribute__((aligned(16))) T As[2][NP][BM * LDK];
   __shared__ __attribute__((aligned(16))) T Bs[2][NP][BN * LDK];
 
-  // --- which problem / tile / K chunk --------------------------------------
-  // Workgroups are dispatched round-robin over the 8 XCDs, each with its own
-  // L2: remap so every XCD works through a contiguous range of logical tiles.
-  const int total = batch.total_tiles;
-  const int hw = blockIdx.x;
-  const int xcd = hw % kNumXcd, kx = hw / kNumXcd;
-  const int q8 = total / kNumXcd, rem8 = total % kNumXcd;
-  const int bid = xcd < rem8 ? xcd * (q8 + 1) + kx : rem8 * (q8 + 1) + (xcd - rem8) * q8 + kx;
-  int g = 0;
-#pragma unroll
-  for (int q = 1; q < kMaxGemmProbs; ++q)
-    if (q < batch.count && bid >= batch.p[q].tile_begin) g = q;
-  const GemmProb &P = batch.p[g];
-  int local = bid - P.tile_begin;
+  // --- which tile / K chunk --------------------------------------------------
   const int per_split = P.tiles_m * P.tiles_n;
   const int split = local / per_split;
   local -= split * per_split;
@@ -229,6 +220,46 @@ gemm_nt_kernel(const GemmBatch batch) {
   }
 }
 
+// Workgroups are dispatched round-robin over the 8 XCDs, each with its own L2:
+// logical index of hardware workgroup hw in a grid of n, such that every XCD
+// works through a contiguous range of logical indices.
+__device__ inline int xcd_logical(int hw, int n) {
+  const int xcd = hw % kNumXcd, kx = hw / kNumXcd;
+  const int q8 = n / kNumXcd, rem8 = n % kNumXcd;
+  return xcd < rem8 ? xcd * (q8 + 1) + kx : rem8 * (q8 + 1) + (xcd - rem8) * q8 + kx;
+}
+
+// One workgroup per tile; the (at most kMaxGemmProbs) problems travel by value.
+template <class Tr, int BM, int BN, int BK>
+__global__ void __launch_bounds__(256)
+gemm_nt_kernel(const GemmBatch batch) {
+  const int bid = xcd_logical(blockIdx.x, batch.total_tiles);
+  int g = 0;
+#pragma unroll
+  for (int q = 1; q < kMaxGemmProbs; ++q)
+    if (q < batch.count && bid >= batch.p[q].tile_begin) g = q;
+  gemm_tile<Tr, BM, BN, BK>(batch.p[g], bid - batch.p[g].tile_begin);
+}
+
+// Persistent form for many problems: a grid sized to the resident capacity
+// walks the global tile list (problems ordered by decreasing K, so the long
+// tiles go first); workgroup w takes logical tiles w, w + G, w + 2G, ...
+template <class Tr, int BM, int BN, int BK>
+__global__ void __launch_bounds__(256)
+gemm_nt_persistent(const GemmProb *__restrict__ probs, int count, int total) {
+  const int G = gridDim.x;
+  for (int t = xcd_logical(blockIdx.x, G); t < total; t += G) {
+    int lo = 0, hi = count - 1;
+    while (lo < hi) {
+      const int mid = (lo + hi + 1) >> 1;
+      if (probs[mid].tile_begin <= t) lo = mid; else hi = mid - 1;
+    }
+    const GemmProb P = probs[lo];
+    gemm_tile<Tr, BM, BN, BK>(P, t - P.tile_begin);
+    __syncthreads();  // the next tile restages LDS
+  }
+}
+
 // ---------------------------------------------------------------------------
 // Configurations
 // ---------------------------------------------------------------------------
@@ -241,6 +272,25 @@ constexpr Cfg kCfgBF[] = {{128, 128, 32}, {64, 64, 32}, {128, 64, 32}};
 template <class Tr, int BM, int BN, int BK>
 hipError_t launch_one(const GemmBatch &b, hipStream_t s) {
   hipLaunchKernelGGL((gemm_nt_kernel<Tr, BM, BN, BK>), dim3(b.total_tiles), dim3(256), 0, s, b);
+  return hipGetLastError();
+}
+
+template <class Tr, int BM, int BN, int BK>
+hipError_t launch_persistent(const GemmProb *dprobs, int count, int total, hipStream_t s) {
+  static int grid = 0;  // resident workgroups on the whole device (per instantiation)
+  if (grid == 0) {
+    int dev = 0, cus = 0, per_cu = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    if (e == hipSuccess)
+      e = hipOccupancyMaxActiveBlocksPerMultiprocessor(
+          &per_cu, reinterpret_cast<const void *>(&gemm_nt_persistent<Tr, BM, BN, BK>), 256, 0);
+    if (e != hipSuccess) return e;
+    grid = std::max(kNumXcd, (cus * std::max(per_cu, 1)) / kNumXcd * kNumXcd);
+  }
+  const int g = std::min(grid, (int)round_up(total, kNumXcd));
+  hipLaunchKernelGGL((gemm_nt_persistent<Tr, BM, BN, BK>), dim3(g), dim3(256), 0, s, dprobs, count,
+                     total);
   return hipGetLastError();
 }
 }  // namespace
@@ -278,6 +328,38 @@ hipError_t gemm_launch(GemmPrec prec, int cfg, GemmBatch &b, hipStream_t s) {
     case 0: return launch_one<TR, CFGS[0].bm, CFGS[0].bn, CFGS[0].bk>(b, s);               \
     case 1: return launch_one<TR, CFGS[1].bm, CFGS[1].bn, CFGS[1].bk>(b, s);               \
     default: return launch_one<TR, CFGS[2].bm, CFGS[2].bn, CFGS[2].bk>(b, s);              \
+  }
+  if (prec == GEMM_F64) { ACSE_GEMM_CASE(TrF64, kCfgF64) }
+  if (prec == GEMM_F32) { ACSE_GEMM_CASE(TrF32, kCfgF32) }
+  ACSE_GEMM_CASE(TrBF16x3, kCfgBF)
+#undef ACSE_GEMM_CASE
+}
+
+hipError_t gemm_launch_persistent(GemmPrec prec, int cfg, std::vector<GemmProb> &probs,
+                                  GemmProb *host_stage, GemmProb *dprobs, hipStream_t s) {
+  const GemmTileInfo ti = gemm_tile_info(prec, cfg);
+  // longest K first; ties keep the caller's order
+  std::stable_sort(probs.begin(), probs.end(),
+                   [](const GemmProb &a, const GemmProb &b) { return a.Kp > b.Kp; });
+  int total = 0;
+  for (GemmProb &p : probs) {
+    p.tiles_m = (p.M + ti.bm - 1) / ti.bm;
+    p.tiles_n = (p.N + ti.bn - 1) / ti.bn;
+    if (p.ksplit < 1) p.ksplit = 1;
+    if (p.kchunk <= 0) p.kchunk = p.Kp;
+    p.tile_begin = total;
+    total += p.tiles_m * p.tiles_n * p.ksplit;
+  }
+  if (total == 0) return hipSuccess;
+  const int count = (int)probs.size();
+  std::copy(probs.begin(), probs.end(), host_stage);
+  hipError_t e = hipMemcpyAsync(dprobs, host_stage, count * sizeof(GemmProb), hipMemcpyHostToDevice, s);
+  if (e != hipSuccess) return e;
+#define ACSE_GEMM_CASE(TR, CFGS)                                                              \
+  switch (cfg) {                                                                              \
+    case 0: return launch_persistent<TR, CFGS[0].bm, CFGS[0].bn, CFGS[0].bk>(dprobs, count, total, s); \
+    case 1: return launch_persistent<TR, CFGS[1].bm, CFGS[1].bn, CFGS[1].bk>(dprobs, count, total, s); \
+    default: return launch_persistent<TR, CFGS[2].bm, CFGS[2].bn, CFGS[2].bk>(dprobs, count, total, s); \
   }
   if (prec == GEMM_F64) { ACSE_GEMM_CASE(TrF64, kCfgF64) }
   if (prec == GEMM_F32) { ACSE_GEMM_CASE(TrF32, kCfgF32) }
