@@ -178,174 +178,173 @@ __global__ void k_f_reduce(int r, const double *__restrict__ part, double *__res
 // Mode product:  out[a, x, b] = alpha * sum_y M(x, y) * (c1 in1 + c2 in2)[a, y, b]
 // in* contiguous [A][r][Bn]; M(x,y) = g[x*r+y] or g[y*r+x] (transposed);
 // output element address (a/adiv)*so1 + (a%adiv)*so0 + x*sx + b*sb.
-// A block owns kModeCols consecutive (a,b) columns.  The r x kModeCols input
-// panel and M^T are staged in LDS (every input element is read once); each
-// thread accumulates a 4 (x) x 4 (column) register tile; the result panel is
-// staged back through LDS and written with lanes along whichever of x or the
-// columns is contiguous in the output.
+//
+// A small dense contraction (2r flops per output) over a long stream of
+// columns (a,b), bound by HBM.  It runs on the FP64 MFMA (16x16x4): M is the
+// A operand and stays in registers for the whole kernel (wave w holds row
+// blocks w and w + 4 of M, one fragment per K step of 4); the input panel of
+// COLS columns is staged in LDS and feeds the B fragments (one double per lane
+// per MFMA, so LDS traffic stays far below its bandwidth).  Persistent blocks
+// walk the panels; the next panel's global loads are in flight into registers
+// while the current one is multiplied.  Results are stored from the
+// accumulators (16 consecutive columns per row and instruction).
 // ---------------------------------------------------------------------------
-constexpr int kModeCols = 64;
 constexpr int kStage = 8;  // global loads in flight per thread in LDS staging loops
 
-template <class O>
+typedef double mode_d4 __attribute__((ext_vector_type(4)));
+
+template <int COLS>
+struct ModeShape {
+  static constexpr int LDT = COLS + 1;   // odd panel row stride (conflict-free deposits)
+  static constexpr int YS = 256 / COLS;  // rows per pass of the strided loader
+  static constexpr int PF = 8;           // prefetched elements per thread (r * COLS <= 2048)
+  static constexpr int CB = COLS / 16;   // MFMA column blocks per panel
+};
+
+template <class O, int COLS, int NRB, bool HAS2>
 __global__ void __launch_bounds__(256)
-k_mode(ModeArgs m, O out) {
+k_mode(ModeArgs m, O out, int npanels) {
+  using S = ModeShape<COLS>;
+  constexpr int KSMAX = (16 * 4 * NRB) / 4;  // K steps of 4 for r <= 64 NRB
   extern __shared__ double mode_smem[];
   const int r = m.r;
-  const int rp = (r + 3) & ~3;
-  double *Mt = mode_smem;                 // [y][x], x padded to rp
-  double *T = mode_smem + r * rp;         // [y][c]; reused as the output panel [x][c]
-  // column indices fit in 32 bits (A * Bn <= r^4)
-  const int Bn = (int)m.Bn;
-  const int ncols = (int)(m.A * m.Bn);
-  const int c0 = blockIdx.x * kModeCols;
-  const int nc = min(kModeCols, ncols - c0);
+  const int ks_n = (r + 3) >> 2;
+  double *T = mode_smem;  // [4 * ks_n][LDT] input panel; rows >= r stay zero
   const int tid = threadIdx.x;
-  // a missing second input reads the first one with weight zero
-  const double *in2 = m.in2 ? m.in2 : m.in1;
-  const double c1 = m.c1, c2 = m.in2 ? m.c2 : 0.0;
+  const int lane = tid & 63, wave = tid >> 6;
+  const int lr = lane & 15, lk = lane >> 4;
+  const int Bn = (int)m.Bn;
+  const int ncols = (int)(m.A * m.Bn);   // A * Bn <= r^4 < 2^31
+  const double c1 = m.c1, c2 = m.c2;
+  const double *in2 = m.in2;
 
-  // --- M^T into LDS: flat walk over (y, x) without divisions per element
-  {
-    int y = tid / rp, x = tid - (tid / rp) * rp;
-    const int dy = 256 / rp, dx = 256 - dy * rp;
-    for (int base = 0; base < r * rp; base += 256 * kStage) {
-      double v[kStage];
-      bool ok[kStage];
-      int yy[kStage], xx[kStage];
+  // A fragments: lane holds M(x = 16 rb + lr, y = 4 ks + lk)
+  double afr[NRB][KSMAX];
 #pragma unroll
-      for (int u = 0; u < kStage; ++u) {
-        yy[u] = y; xx[u] = x;
-        ok[u] = y < r && x < r;
-        v[u] = ld_ok(m.g, m.transpose_m ? y * r + x : x * r + y, ok[u]);
-        y += dy; x += dx;
-        if (x >= rp) { x -= rp; ++y; }
-      }
+  for (int q = 0; q < NRB; ++q) {
+    const int x = (wave + 4 * q) * 16 + lr;
 #pragma unroll
-      for (int u = 0; u < kStage; ++u)
-        if (yy[u] < r) Mt[yy[u] * rp + xx[u]] = ok[u] ? v[u] : 0.0;
+    for (int ks = 0; ks < KSMAX; ++ks) {
+      const int y = ks * 4 + lk;
+      const bool ok = x < r && y < r;
+      const double v = ld_ok(m.g, m.transpose_m ? (int64_t)y * r + x : (int64_t)x * r + y, ok);
+      afr[q][ks] = ok ? v : 0.0;
     }
   }
-  // --- input panel T[y][c] = (c1 in1 + c2 in2)[a, y, b] for column c0 + c = a*Bn + b
-  if (Bn == 1) {
-    // the panel is one contiguous run in[c0*r + f], f = c*r + y
-    const int64_t base_off = (int64_t)c0 * r;
-    const int tot = nc * r;
-    int c = tid / r, y = tid - (tid / r) * r;
-    const int dc = 256 / r, dy = 256 - dc * r;
-    for (int f0 = 0; f0 < r * kModeCols; f0 += 256 * kStage) {
-      double v1[kStage], v2[kStage];
-      int cc[kStage], yy[kStage];
-      bool ok[kStage];
+  for (int e = r * S::LDT + tid; e < 4 * ks_n * S::LDT; e += 256) T[e] = 0.0;
+
+  // flat walk (Bn == 1): element f of the panel is column f / r, row f % r
+  const int dc = 256 / r, dy = 256 - (256 / r) * r;
+  const int c_first = tid / r, y_first = tid - (tid / r) * r;
+
+  double v1[S::PF], v2[HAS2 ? S::PF : 1];
+  auto fetch = [&](int p) {
+    const int c0 = p * COLS;
+    const int nc = min(COLS, ncols - c0);
+    if (Bn == 1) {
+      const int64_t base = (int64_t)c0 * r;
+      const int tot = nc * r;
 #pragma unroll
-      for (int u = 0; u < kStage; ++u) {
-        const int f = f0 + u * 256 + tid;
-        cc[u] = c; yy[u] = y;
-        ok[u] = f < tot;
-        v1[u] = ld_ok(m.in1, base_off + f, ok[u]);
-        v2[u] = ld_ok(in2, base_off + f, ok[u]);
-        y += dy; c += dc;
+      for (int k = 0; k < S::PF; ++k) {
+        const int f = tid + k * 256;
+        v1[k] = ld_ok(m.in1, base + f, f < tot);
+        if constexpr (HAS2) v2[k] = ld_ok(in2, base + f, f < tot);
+      }
+    } else {
+      const int c = tid % COLS;
+      const bool okc = c < nc;
+      const int col = c0 + (okc ? c : 0);
+      const int a = col / Bn, b = col - (col / Bn) * Bn;
+      const int64_t off0 = (int64_t)a * r * Bn + b;
+#pragma unroll
+      for (int k = 0; k < S::PF; ++k) {
+        const int y = tid / COLS + k * S::YS;
+        const bool ok = okc && y < r;
+        v1[k] = ld_ok(m.in1, off0 + (int64_t)y * Bn, ok);
+        if constexpr (HAS2) v2[k] = ld_ok(in2, off0 + (int64_t)y * Bn, ok);
+      }
+    }
+  };
+  auto combine = [&](int k) {
+    if constexpr (HAS2) return c1 * v1[k] + c2 * v2[k];
+    else return c1 * v1[k];
+  };
+  auto deposit = [&](int p) {
+    const int nc = min(COLS, ncols - p * COLS);
+    if (Bn == 1) {
+      const int tot = nc * r;
+      int c = c_first, y = y_first;
+#pragma unroll
+      for (int k = 0; k < S::PF; ++k) {
+        const int f = tid + k * 256;
+        if (c < COLS) T[y * S::LDT + c] = f < tot ? combine(k) : 0.0;
+        c += dc;
+        y += dy;
         if (y >= r) { y -= r; ++c; }
       }
+    } else {
+      const int c = tid % COLS;
 #pragma unroll
-      for (int u = 0; u < kStage; ++u)
-        if (cc[u] < kModeCols) T[yy[u] * kModeCols + cc[u]] = ok[u] ? c1 * v1[u] + c2 * v2[u] : 0.0;
-    }
-  } else {
-    // each thread owns one column (lanes along consecutive b), rows y step by 4
-    const int c = tid & (kModeCols - 1);
-    const bool okc = c < nc;
-    const int col = c0 + (okc ? c : 0);
-    const int a = col / Bn, b = col - a * Bn;
-    const int64_t off0 = ((int64_t)a * r) * Bn + b;
-    const int ystep = 256 / kModeCols;
-    for (int y0 = tid / kModeCols; y0 < r; y0 += ystep * kStage) {
-      double v1[kStage], v2[kStage];
-#pragma unroll
-      for (int u = 0; u < kStage; ++u) {
-        const int y = y0 + u * ystep;
-        const bool ok = okc && y < r;
-        const int64_t off = off0 + (int64_t)y * Bn;
-        v1[u] = ld_ok(m.in1, off, ok);
-        v2[u] = ld_ok(in2, off, ok);
-      }
-#pragma unroll
-      for (int u = 0; u < kStage; ++u) {
-        const int y = y0 + u * ystep;
-        if (y < r) T[y * kModeCols + c] = okc ? c1 * v1[u] + c2 * v2[u] : 0.0;
+      for (int k = 0; k < S::PF; ++k) {
+        const int y = tid / COLS + k * S::YS;
+        if (y < r) T[y * S::LDT + c] = c < nc ? combine(k) : 0.0;
       }
     }
-  }
+  };
+
+  int p = blockIdx.x;
+  fetch(p);
+  deposit(p);
   __syncthreads();
-  // --- 4 x 4 register tiles: rows x = xg..xg+3, columns cg..cg+3
-  const int cg = (tid & 15) * 4;
-  const int xg0 = (tid >> 4) * 4;
-  double acc[2][4][4];
-#pragma unroll
-  for (int u = 0; u < 2; ++u)
-#pragma unroll
-    for (int i = 0; i < 4; ++i)
-#pragma unroll
-      for (int j = 0; j < 4; ++j) acc[u][i][j] = 0.0;
-#pragma unroll
-  for (int u = 0; u < 2; ++u) {
-    const int xg = xg0 + u * 64;
-    if (xg >= r) break;
-    const double *mp = Mt + xg;
-    const double *tp = T + cg;
-    for (int y = 0; y < r; ++y) {
-      double mv[4], tv[4];
-#pragma unroll
-      for (int i = 0; i < 4; ++i) mv[i] = mp[i];
-#pragma unroll
-      for (int j = 0; j < 4; ++j) tv[j] = tp[j];
-      mp += rp;
-      tp += kModeCols;
-#pragma unroll
-      for (int i = 0; i < 4; ++i)
-#pragma unroll
-        for (int j = 0; j < 4; ++j) acc[u][i][j] += mv[i] * tv[j];
-    }
-  }
-  __syncthreads();
-#pragma unroll
-  for (int u = 0; u < 2; ++u) {
-    const int xg = xg0 + u * 64;
-    if (xg >= r) break;
-#pragma unroll
-    for (int i = 0; i < 4; ++i)
-      if (xg + i < r)
-#pragma unroll
-        for (int j = 0; j < 4; ++j) T[(xg + i) * kModeCols + cg + j] = acc[u][i][j];
-  }
-  __syncthreads();
-  // --- store: lanes along columns (output contiguous in (a,b)) or along x
   const double alpha = m.alpha;
-  if (m.out_cols_fast) {
-    const int c = tid & (kModeCols - 1);
-    if (c < nc) {
-      const int col = c0 + c;
-      const int a = col / Bn, b = col - a * Bn;
-      const int adiv = (int)m.adiv;
-      const int a1 = a / adiv, a0 = a - a1 * adiv;
-      const int64_t off0 = (int64_t)a1 * m.so1 + (int64_t)a0 * m.so0 + (int64_t)b * m.sb;
-      for (int x = tid / kModeCols; x < r; x += 256 / kModeCols)
-        out.put(off0 + (int64_t)x * m.sx, alpha * T[x * kModeCols + c]);
+  const int adiv = (int)m.adiv;
+  for (;;) {
+    const int pn = p + (int)gridDim.x;
+    const bool more = pn < npanels;
+    if (more) fetch(pn);
+    mode_d4 acc[NRB][S::CB];
+#pragma unroll
+    for (int q = 0; q < NRB; ++q)
+#pragma unroll
+      for (int cb = 0; cb < S::CB; ++cb) acc[q][cb] = mode_d4{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int ks = 0; ks < KSMAX; ++ks) {
+      if (ks < ks_n) {
+        const double *tp = T + (ks * 4 + lk) * S::LDT + lr;
+#pragma unroll
+        for (int cb = 0; cb < S::CB; ++cb) {
+          const double bfr = tp[cb * 16];
+#pragma unroll
+          for (int q = 0; q < NRB; ++q)
+            acc[q][cb] = __builtin_amdgcn_mfma_f64_16x16x4f64(afr[q][ks], bfr, acc[q][cb], 0, 0, 0);
+        }
+      }
     }
-  } else {
-    // x fastest: flat walk over (c, x)
-    int c = tid / r, x = tid - (tid / r) * r;
-    const int dc = 256 / r, dx = 256 - dc * r;
-    const int adiv = (int)m.adiv;
-    for (int f = tid; f < nc * r; f += 256) {
-      const int col = c0 + c;
-      const int a = col / Bn, b = col - a * Bn;
-      const int a1 = a / adiv, a0 = a - a1 * adiv;
-      const int64_t off = (int64_t)a1 * m.so1 + (int64_t)a0 * m.so0 + (int64_t)x * m.sx + (int64_t)b * m.sb;
-      out.put(off, alpha * T[x * kModeCols + c]);
-      x += dx; c += dc;
-      if (x >= r) { x -= r; ++c; }
+    // store: accumulator item v of lane l is row lk + 4v of the block, column lr
+    const int c0 = p * COLS;
+    const int nc = min(COLS, ncols - c0);
+#pragma unroll
+    for (int cb = 0; cb < S::CB; ++cb) {
+      const int cc = cb * 16 + lr;
+      if (cc < nc) {
+        const int col = c0 + cc;
+        const int a = col / Bn, b = col - (col / Bn) * Bn;
+        const int a1 = a / adiv, a0 = a - (a / adiv) * adiv;
+        const int64_t base = (int64_t)a1 * m.so1 + (int64_t)a0 * m.so0 + (int64_t)b * m.sb;
+#pragma unroll
+        for (int q = 0; q < NRB; ++q)
+#pragma unroll
+          for (int v = 0; v < 4; ++v) {
+            const int x = (wave + 4 * q) * 16 + lk + 4 * v;
+            if (x < r) out.put(base + (int64_t)x * m.sx, alpha * acc[q][cb][v]);
+          }
+      }
     }
+    if (!more) break;
+    __syncthreads();  // every wave is done reading the panel
+    deposit(pn);
+    __syncthreads();
+    p = pn;
   }
 }
 
@@ -804,29 +803,52 @@ hipError_t launch_f(int r, const double *Aaa, const double *Aab, const double *g
   return hipGetLastError();
 }
 
-size_t mode_lds_bytes(int r) { return (size_t)(r * ((r + 3) & ~3) + r * kModeCols) * sizeof(double); }
+// r <= 64: one 16-row block of M per wave, 32-column panels; r <= 96: two
+// row blocks per wave, 16-column panels (the prefetch stays at 8 per thread).
+static int mode_cols(int r) { return r <= 64 ? 32 : 16; }
+
+size_t mode_lds_bytes(int r) {
+  const int ldt = mode_cols(r) + 1;
+  return (size_t)(4 * ((r + 3) / 4) * ldt) * sizeof(double);
+}
+
+template <class O, int COLS, int NRB, bool HAS2>
+static hipError_t launch_mode_t(const ModeArgs &m, O out, hipStream_t s) {
+  static int resident[kModeMaxR + 1] = {};  // blocks the device holds at once, by r
+  const size_t lds = mode_lds_bytes(m.r);
+  int &res = resident[m.r];
+  if (res == 0) {
+    const void *fn = reinterpret_cast<const void *>(&k_mode<O, COLS, NRB, HAS2>);
+    int dev = 0, cus = 0, per_cu = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    if (e == hipSuccess) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, 256, lds);
+    if (e != hipSuccess) return e;
+    res = cus * std::max(per_cu, 1);
+  }
+  const int64_t ncols = m.A * m.Bn;
+  const int npanels = (int)((ncols + COLS - 1) / COLS);
+  if (npanels == 0) return hipSuccess;
+  hipLaunchKernelGGL((k_mode<O, COLS, NRB, HAS2>), dim3(std::min(npanels, res)), dim3(256), lds, s, m,
+                     out, npanels);
+  return hipGetLastError();
+}
+
+template <class O>
+static hipError_t launch_mode_o(const ModeArgs &m, O out, hipStream_t s) {
+  if (m.in2)
+    return m.r <= 64 ? launch_mode_t<O, 32, 1, true>(m, out, s) : launch_mode_t<O, 16, 2, true>(m, out, s);
+  return m.r <= 64 ? launch_mode_t<O, 32, 1, false>(m, out, s) : launch_mode_t<O, 16, 2, false>(m, out, s);
+}
 
 hipError_t launch_mode(GemmPrec prec, const ModeArgs &m, const OperandRef &out, hipStream_t s) {
-  if (m.r > kModeMaxR) return hipErrorInvalidValue;
-  const int64_t ncols = (int64_t)m.A * m.Bn;
-  const dim3 grid((unsigned)((ncols + kModeCols - 1) / kModeCols));
-  const size_t lds = mode_lds_bytes(m.r);
+  if (m.r < 2 || m.r > kModeMaxR) return hipErrorInvalidValue;
   if (m.accumulate) {
     if (prec != GEMM_F64) return hipErrorInvalidValue;
-    using O = OutF64Acc;
-    hipError_t err = hipFuncSetAttribute(reinterpret_cast<const void *>(&k_mode<O>),
-                                         hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-    if (err != hipSuccess) return err;
-    hipLaunchKernelGGL((k_mode<O>), grid, dim3(256), lds, s, m, O{static_cast<double *>(out.hi)});
-    return hipGetLastError();
+    return launch_mode_o(m, OutF64Acc{static_cast<double *>(out.hi)}, s);
   }
-  ACSE_DISPATCH_OUT(prec, {
-    hipError_t err = hipFuncSetAttribute(reinterpret_cast<const void *>(&k_mode<O>),
-                                         hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-    if (err != hipSuccess) return err;
-    hipLaunchKernelGGL((k_mode<O>), grid, dim3(256), lds, s, m, make_out<O>(out));
-  });
-  return hipGetLastError();
+  ACSE_DISPATCH_OUT(prec, return launch_mode_o(m, make_out<O>(out), s));
+  return hipSuccess;
 }
 
 hipError_t launch_g2(GemmPrec prec, int r, int ld, const double *Aaa, const double *Aab,
