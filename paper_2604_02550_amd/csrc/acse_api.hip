@@ -32,7 +32,9 @@ using namespace acse;
 
 namespace {
 
-constexpr int kNat = 26;  // natural r^4 arrays in Workspace
+constexpr int kNat = 26;     // natural r^4 arrays in Workspace
+constexpr int kNumOps = 12;  // GEMM operand buffers in Workspace
+constexpr int kProbsPerMap = 6;  // pair-index products of one residual map
 
 struct Workspace {
   // natural FP64 r^4 arrays
@@ -40,7 +42,7 @@ struct Workspace {
   double *Zaa, *Zab, *Pp, *Pm, *E3, *Saa, *Sab;
   double *Raa, *Rab, *Maa, *Mab, *Uaa, *Uab, *Naa, *Nab;
   // GEMM operand buffers (sized for FP64, reused by the narrower formats)
-  char *op[10];
+  char *op[12];
   // small arrays
   double *fpart, *f, *tpart, *t, *partial, *scal;
 };
@@ -142,7 +144,7 @@ int64_t carve(char *p, int r, bool full, Workspace &w) {
                          &w.Raa, &w.Rab, &w.Maa, &w.Mab, &w.Uaa, &w.Uab, &w.Naa, &w.Nab};
   const int nnat = full ? kNat : kNat - 6;
   for (int k = 0; k < kNat; ++k) *nats[k] = k < nnat ? reinterpret_cast<double *>(take(nat)) : nullptr;
-  for (int k = 0; k < 10; ++k) w.op[k] = take(opb);
+  for (int k = 0; k < kNumOps; ++k) w.op[k] = take(opb);
   w.fpart = reinterpret_cast<double *>(take(round_up((int64_t)r * r2 * 8, 256)));
   w.f = reinterpret_cast<double *>(take(round_up(r2 * 8, 256)));
   w.tpart = reinterpret_cast<double *>(take(round_up((int64_t)t_partial_blocks() * r2 * 8, 256)));
@@ -157,7 +159,7 @@ OperandRef operand(const Workspace &w, int idx, GemmPrec prec, int r) {
   if (prec == GEMM_BF16X3) o.lo = w.op[idx] + op_rows(r) * op_ld(r) * 2;
   return o;
 }
-enum { OP_DAA, OP_DAB, OP_BAA, OP_BAB, OP_LP, OP_LM, OP_L3, OP_RP, OP_RM, OP_R3 };
+enum { OP_DAA, OP_DS, OP_DA, OP_BAA, OP_BS, OP_BA, OP_LP, OP_LM, OP_L3, OP_RP, OP_RM, OP_R3 };
 
 acse_status validate(acse_ctx c, const acse_problem *p, const acse_options *o, bool need_d1 = true) {
   if (!c) return ACSE_ERR_ARG;
@@ -208,8 +210,8 @@ acse_status prep_rdm_operands(acse_ctx c, const acse_problem *p, GemmPrec prec, 
   HIP_TRY(c, launch_w_natural(r, p->d1, p->d2aa, p->d2ab, w.Waa, w.Wab, c->stream));
   HIP_TRY(c, launch_w_ph(prec, r, ld, p->d1, p->d2aa, p->d2ab, operand(w, OP_RP, prec, r),
                          operand(w, OP_RM, prec, r), operand(w, OP_R3, prec, r), c->stream));
-  HIP_TRY(c, launch_d_operand(prec, r, ld, p->d2aa, p->d2ab, operand(w, OP_DAA, prec, r),
-                              operand(w, OP_DAB, prec, r), c->stream));
+  HIP_TRY(c, launch_d_operand(prec, r, p->d2aa, p->d2ab, operand(w, OP_DAA, prec, r),
+                              operand(w, OP_DS, prec, r), operand(w, OP_DA, prec, r), c->stream));
   return ACSE_OK;
 }
 
@@ -244,8 +246,9 @@ acse_status map_front(acse_ctx c, const acse_problem *p, GemmPrec prec, const do
       m.so1 = r3; m.so0 = 0; m.sx = r2; m.sb = 1; m.out_cols_fast = 1;
       HIP_TRY(c, launch_mode(GEMM_F64, m, OperandRef{b ? w.Hab : w.Haa, nullptr}, s));
     }
-    HIP_TRY(c, launch_g2(prec, r, ld, Xaa, Xab, w.Haa, w.Hab, w.f, w.G2aa, w.G2ab,
-                         operand(w, OP_BAA, prec, r), operand(w, OP_BAB, prec, r), s));
+    HIP_TRY(c, launch_g2(prec, r, Xaa, Xab, w.Haa, w.Hab, w.f, w.G2aa, w.G2ab,
+                         operand(w, OP_BAA, prec, r), operand(w, OP_BS, prec, r),
+                         operand(w, OP_BA, prec, r), s));
     // C^T[k,l,i,j] = 4/3 sum_rs g_ir g_js G2[k,l,r,s]
     for (int b = 0; b < 2; ++b) {
       ModeArgs m1 = mode_base(r, g);  // T1[k,l,r,j] = sum_s g[j,s] G2[k,l,r,s]
@@ -276,26 +279,32 @@ acse_status map_front(acse_ctx c, const acse_problem *p, GemmPrec prec, const do
   return ACSE_OK;
 }
 
-// The five pair-index products of F(X) (2 pp + 3 ph) as GEMM descriptors.
+// The six pair-index products of F(X) as GEMM descriptors: three packed pp
+// products (Z_aa over pairs i<j and K r<s; the alpha-beta block split into its
+// parts symmetric (i<=j, r<=s) and antisymmetric (i<j, r<s) under the pair
+// exchange) and the three ph products.
 void map_probs(const Workspace &w, GemmPrec prec, int r, GemmProb *out) {
   const int64_t r2 = (int64_t)r * r, r3 = r2 * r;
-  const int ld = (int)op_ld(r);
-  auto set = [&](int q, int ia, int ib, double alpha, double *C, int64_t sm1, int64_t sm0,
-                 int64_t sn1, int64_t sn0) {
+  auto set = [&](int q, int ia, int ib, double alpha, double *C, int M, int ld, int64_t sm1,
+                 int64_t sm0, int64_t sn1, int64_t sn0) {
     GemmProb &P = out[q];
     P = GemmProb{};
     OperandRef a = operand(w, ia, prec, r), bb = operand(w, ib, prec, r);
     P.A = a.hi; P.A2 = a.lo; P.B = bb.hi; P.B2 = bb.lo;
     P.C = C; P.alpha = alpha;
-    P.M = (int)r2; P.N = (int)r2; P.Kp = ld; P.ld = ld; P.rdiv = r;
+    P.M = M; P.N = (int)r2; P.Kp = ld; P.ld = ld; P.rdiv = r;
     P.sm1 = sm1; P.sm0 = sm0; P.sn1 = sn1; P.sn0 = sn0;
     P.ksplit = 1; P.kchunk = ld; P.accumulate = 0;
   };
-  set(0, OP_DAA, OP_BAA, 2.0, w.Zaa, r3, r2, r, 1);   // rows (i,j), cols (k,l)
-  set(1, OP_DAB, OP_BAB, 4.0, w.Zab, r3, r2, r, 1);
-  set(2, OP_LP, OP_RP, 1.0, w.Pp, r, r3, r2, 1);      // rows (k,i), cols (j,l) -> [i,j,k,l]
-  set(3, OP_LM, OP_RM, 1.0, w.Pm, r, r3, r2, 1);
-  set(4, OP_L3, OP_R3, -2.0, w.E3, r, r2, r3, 1);     // rows (k,j), cols (i,l) -> [i,j,k,l]
+  const int nlt = npair_lt(r), nle = npair_le(r);
+  const int ldlt = (int)ld_pair_lt(r), ldle = (int)ld_pair_le(r), ld = (int)op_ld(r);
+  // packed rows p -> C + p r^2 + (k r + l)
+  set(0, OP_DAA, OP_BAA, 2.0, w.Zaa, nlt, ldlt, r3, r2, r, 1);
+  set(1, OP_DS, OP_BS, 4.0, w.Zab, nle, ldle, r3, r2, r, 1);
+  set(2, OP_DA, OP_BA, 4.0, w.Zab + (int64_t)nle * r2, nlt, ldlt, r3, r2, r, 1);
+  set(3, OP_LP, OP_RP, 1.0, w.Pp, (int)r2, ld, r, r3, r2, 1);    // rows (k,i), cols (j,l) -> [i,j,k,l]
+  set(4, OP_LM, OP_RM, 1.0, w.Pm, (int)r2, ld, r, r3, r2, 1);
+  set(5, OP_L3, OP_R3, -2.0, w.E3, (int)r2, ld, r, r2, r3, 1);   // rows (k,j), cols (i,l) -> [i,j,k,l]
 }
 
 // Stage 4 of F(X): assembly, (ij) <-> (kl) exchange, mask and the FP64 norm
@@ -306,7 +315,8 @@ acse_status map_back(acse_ctx c, const acse_problem *p, double sigma, double *Oa
   const int r = p->r;
   hipStream_t s = c->stream;
   StageTimer t4(c, 4);
-  HIP_TRY(c, launch_assemble(r, p->d1, w.t, w.Zaa, w.Zab, w.Pp, w.Pm, w.E3, w.Saa, w.Sab, s));
+  HIP_TRY(c, launch_assemble(r, p->d1, w.t, w.Zaa, w.Zab, w.Zab + (int64_t)npair_le(r) * r * r, w.Pp,
+                             w.Pm, w.E3, w.Saa, w.Sab, s));
   HIP_TRY(c, launch_finish(r, sigma, w.Saa, w.Sab, w.Caa, w.Cab, Oaa, Oab, act, Maa, Mab,
                            w.partial, norm_out, s));
   return ACSE_OK;
@@ -324,7 +334,7 @@ acse_status run_map(acse_ctx c, const acse_problem *p, GemmPrec prec, int cfg, c
   acse_status st = map_front(c, p, prec, Xaa, Xab, w);
   if (st != ACSE_OK) return st;
   GemmBatch batch{};
-  batch.count = 5;
+  batch.count = kProbsPerMap;
   map_probs(w, prec, r, batch.p);
   int use_cfg = cfg;
   if (use_cfg < 0) {
@@ -407,7 +417,7 @@ acse_status acse_create(acse_ctx *out, int device, void *hip_stream, int32_t r_m
   carve(static_cast<char *>(c->base), r_max, true, w);
   const int64_t opb = c->op_bytes;
   // Operand padding rows are read by full tiles: give every byte a defined value once.
-  if (launch_fill((10 * opb) / 8, 0.0, reinterpret_cast<double *>(w.op[0]), c->stream) != hipSuccess ||
+  if (launch_fill((kNumOps * opb) / 8, 0.0, reinterpret_cast<double *>(w.op[0]), c->stream) != hipSuccess ||
       hipStreamSynchronize(c->stream) != hipSuccess) {
     (void)hipFree(c->base);
     delete c;
@@ -743,7 +753,8 @@ extern "C" acse_status acse_residual_vjp(acse_ctx ctx, const acse_problem *prob,
   for (int b = 0; b < 2; ++b)
     HIP_TRY(ctx, mode(b ? w.Aab : w.Aaa, nullptr, 0.0, g, 1, r, r2, 1.0, b ? w.Hab : w.Haa, 1, r3, 0,
                       r2, 1, 1, 0));
-  HIP_TRY(ctx, launch_g2(prec, r, ld, w.Aaa, w.Aab, w.Haa, w.Hab, w.f, w.G2aa, w.G2ab, vop(0), vop(1), s));
+  HIP_TRY(ctx, launch_g2(prec, r, w.Aaa, w.Aab, w.Haa, w.Hab, w.f, w.G2aa, w.G2ab, vop(0), vop(1), vop(2),
+                         s));
   double *Baa = V[0], *Bab = V[1], *Lp = V[2], *Lm = V[3], *L3 = V[4], *Rp = V[5], *Rm = V[6], *R3 = V[7];
   HIP_TRY(ctx, permute(GEMM_F64, natref(Baa), false, w.Aaa, ID, 1.0, w.G2aa, ID, -1.0, 0));
   HIP_TRY(ctx, permute(GEMM_F64, natref(Bab), false, w.Aab, ID, 1.0, w.G2ab, ID, -1.0, 0));
@@ -1031,7 +1042,7 @@ acse_status ensure_batch(acse_ctx c, int count, const acse_problem *probs, Batch
   const int64_t norms_off = need;
   need += round_up((int64_t)count * 8, 256);
   const int64_t probs_off = need;
-  need += round_up((int64_t)count * 5 * (int64_t)sizeof(GemmProb), 256);
+  need += round_up((int64_t)count * kProbsPerMap * (int64_t)sizeof(GemmProb), 256);
   if (need > c->bbytes) {
     if (c->bbase) {
       HIP_TRY(c, hipStreamSynchronize(c->stream));
@@ -1047,16 +1058,16 @@ acse_status ensure_batch(acse_ctx c, int count, const acse_problem *probs, Batch
     c->bbytes = need;
     HIP_TRY(c, launch_fill(need / 8, 0.0, static_cast<double *>(c->bbase), c->stream));
   }
-  if (5 * count > c->hdesc_cap) {
+  if (kProbsPerMap * count > c->hdesc_cap) {
     if (c->hdesc) {
       if (c->hdesc_done) HIP_TRY(c, hipEventSynchronize(c->hdesc_done));
       (void)hipHostFree(c->hdesc);
       c->hdesc = nullptr;
       c->hdesc_cap = 0;
     }
-    HIP_TRY(c, hipHostMalloc(reinterpret_cast<void **>(&c->hdesc), 5 * count * sizeof(GemmProb),
+    HIP_TRY(c, hipHostMalloc(reinterpret_cast<void **>(&c->hdesc), kProbsPerMap * count * sizeof(GemmProb),
                              hipHostMallocDefault));
-    c->hdesc_cap = 5 * count;
+    c->hdesc_cap = kProbsPerMap * count;
   }
   if (!c->hdesc_done) HIP_TRY(c, hipEventCreateWithFlags(&c->hdesc_done, hipEventDisableTiming));
   char *base = static_cast<char *>(c->bbase);
@@ -1079,7 +1090,7 @@ int batch_cfg(acse_ctx c, GemmPrec prec, int count, const acse_problem *probs, i
 acse_status run_batched(acse_ctx c, int count, const acse_problem *probs, GemmPrec prec, int cfg,
                         double *const *Raa, double *const *Rab, BatchPlan &plan) {
   acse_status st;
-  std::vector<GemmProb> gp(5 * (size_t)count);
+  std::vector<GemmProb> gp(kProbsPerMap * (size_t)count);
   for (int i = 0; i < count; ++i) {
     const acse_problem *p = &probs[i];
     Workspace &w = plan.ws[i];
@@ -1089,7 +1100,7 @@ acse_status run_batched(acse_ctx c, int count, const acse_problem *probs, GemmPr
       HIP_TRY(c, launch_fold(p->r, p->n_alpha + p->n_beta, p->h, p->V, w.Aaa, w.Aab, c->stream));
     }
     if ((st = map_front(c, p, prec, w.Aaa, w.Aab, w)) != ACSE_OK) return st;
-    map_probs(w, prec, p->r, &gp[5 * (size_t)i]);
+    map_probs(w, prec, p->r, &gp[kProbsPerMap * (size_t)i]);
   }
   {
     // the pinned staging buffer may still feed the previous call's copy

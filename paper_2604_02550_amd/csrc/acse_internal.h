@@ -36,10 +36,21 @@ struct GemmProb {
 };
 
 constexpr int kMaxGemmProbs = 6;
+constexpr int kGemmXcds = 8;  // XCDs of the device, each with its own L2
+// Logical tile order of a grouped launch: segment s (in order) covers logical
+// tiles [seg_start[s], seg_start[s+1]) = tiles seg_local[s]... of problem
+// seg_prob[s].  Segments take the c-th eighth of every problem for c = 0..7,
+// so the contiguous logical range each XCD receives holds an equal share of
+// every problem (balanced when the problems' K differ).
+constexpr int kMaxGemmSegs = kMaxGemmProbs * kGemmXcds;
 struct GemmBatch {
   GemmProb p[kMaxGemmProbs];
   int count;
   int total_tiles;
+  int nseg;
+  int seg_start[kMaxGemmSegs + 1];
+  int seg_prob[kMaxGemmSegs];
+  int seg_local[kMaxGemmSegs];
 };
 
 // Tile configurations (index = options.tile; -1 picks by size).

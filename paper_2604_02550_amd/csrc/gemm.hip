@@ -44,7 +44,7 @@ __device__ inline typename Tr::Acc acc_zero() {
   return a;
 }
 
-constexpr int kNumXcd = 8;
+constexpr int kNumXcd = kGemmXcds;
 constexpr int kGroupM = 8;
 
 // One BM x BN output tile (and K chunk) of problem P; `local` counts the
@@ -229,23 +229,30 @@ __device__ inline int xcd_logical(int hw, int n) {
   return xcd < rem8 ? xcd * (q8 + 1) + kx : rem8 * (q8 + 1) + (xcd - rem8) * q8 + kx;
 }
 
+// Minimum waves per SIMD the register allocation must allow: the FP64 128 x 128
+// tile (4 x 4 MFMA blocks per wave) is held to two so that two workgroups share
+// a CU and hide each other's K-slab staging.
+template <class Tr, int BM, int BN>
+constexpr int gemm_wpe() { return (sizeof(typename Tr::T) == 8 && BM * BN >= 128 * 128) ? 2 : 1; }
+
 // One workgroup per tile; the (at most kMaxGemmProbs) problems travel by value.
-template <class Tr, int BM, int BN, int BK>
-__global__ void __launch_bounds__(256)
+template <class Tr, int BM, int BN, int BK, int WPE>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WPE)))
 gemm_nt_kernel(const GemmBatch batch) {
   const int bid = xcd_logical(blockIdx.x, batch.total_tiles);
-  int g = 0;
-#pragma unroll
-  for (int q = 1; q < kMaxGemmProbs; ++q)
-    if (q < batch.count && bid >= batch.p[q].tile_begin) g = q;
-  gemm_tile<Tr, BM, BN, BK>(batch.p[g], bid - batch.p[g].tile_begin);
+  int lo = 0, hi = batch.nseg - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (batch.seg_start[mid] <= bid) lo = mid; else hi = mid - 1;
+  }
+  gemm_tile<Tr, BM, BN, BK>(batch.p[batch.seg_prob[lo]], batch.seg_local[lo] + bid - batch.seg_start[lo]);
 }
 
 // Persistent form for many problems: a grid sized to the resident capacity
 // walks the global tile list (problems ordered by decreasing K, so the long
 // tiles go first); workgroup w takes logical tiles w, w + G, w + 2G, ...
-template <class Tr, int BM, int BN, int BK>
-__global__ void __launch_bounds__(256)
+template <class Tr, int BM, int BN, int BK, int WPE>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WPE)))
 gemm_nt_persistent(const GemmProb *__restrict__ probs, int count, int total) {
   const int G = gridDim.x;
   for (int t = xcd_logical(blockIdx.x, G); t < total; t += G) {
@@ -271,7 +278,8 @@ constexpr Cfg kCfgBF[] = {{128, 128, 32}, {64, 64, 32}, {128, 64, 32}};
 
 template <class Tr, int BM, int BN, int BK>
 hipError_t launch_one(const GemmBatch &b, hipStream_t s) {
-  hipLaunchKernelGGL((gemm_nt_kernel<Tr, BM, BN, BK>), dim3(b.total_tiles), dim3(256), 0, s, b);
+  hipLaunchKernelGGL((gemm_nt_kernel<Tr, BM, BN, BK, gemm_wpe<Tr, BM, BN>()>), dim3(b.total_tiles),
+                     dim3(256), 0, s, b);
   return hipGetLastError();
 }
 
@@ -284,13 +292,15 @@ hipError_t launch_persistent(const GemmProb *dprobs, int count, int total, hipSt
     if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
     if (e == hipSuccess)
       e = hipOccupancyMaxActiveBlocksPerMultiprocessor(
-          &per_cu, reinterpret_cast<const void *>(&gemm_nt_persistent<Tr, BM, BN, BK>), 256, 0);
+          &per_cu,
+          reinterpret_cast<const void *>(&gemm_nt_persistent<Tr, BM, BN, BK, gemm_wpe<Tr, BM, BN>()>),
+          256, 0);
     if (e != hipSuccess) return e;
     grid = std::max(kNumXcd, (cus * std::max(per_cu, 1)) / kNumXcd * kNumXcd);
   }
   const int g = std::min(grid, (int)round_up(total, kNumXcd));
-  hipLaunchKernelGGL((gemm_nt_persistent<Tr, BM, BN, BK>), dim3(g), dim3(256), 0, s, dprobs, count,
-                     total);
+  hipLaunchKernelGGL((gemm_nt_persistent<Tr, BM, BN, BK, gemm_wpe<Tr, BM, BN>()>), dim3(g), dim3(256),
+                     0, s, dprobs, count, total);
   return hipGetLastError();
 }
 }  // namespace
@@ -323,6 +333,20 @@ hipError_t gemm_launch(GemmPrec prec, int cfg, GemmBatch &b, hipStream_t s) {
   }
   b.total_tiles = total;
   if (total == 0) return hipSuccess;
+  b.nseg = 0;
+  int start = 0;
+  for (int c = 0; c < kGemmXcds; ++c)
+    for (int q = 0; q < b.count; ++q) {
+      const int n = b.p[q].tiles_m * b.p[q].tiles_n * b.p[q].ksplit;
+      const int lo = (int)((int64_t)n * c / kGemmXcds), hi = (int)((int64_t)n * (c + 1) / kGemmXcds);
+      if (hi <= lo) continue;
+      b.seg_start[b.nseg] = start;
+      b.seg_prob[b.nseg] = q;
+      b.seg_local[b.nseg] = lo;
+      ++b.nseg;
+      start += hi - lo;
+    }
+  b.seg_start[b.nseg] = start;
 #define ACSE_GEMM_CASE(TR, CFGS)                                                          \
   switch (cfg) {                                                                          \
     case 0: return launch_one<TR, CFGS[0].bm, CFGS[0].bn, CFGS[0].bk>(b, s);               \

@@ -34,18 +34,48 @@ hipError_t launch_w_natural(int r, const double *g, const double *d2aa, const do
 hipError_t launch_w_ph(GemmPrec prec, int r, int ld, const double *g, const double *d2aa,
                        const double *d2ab, const OperandRef &Rp, const OperandRef &Rm,
                        const OperandRef &R3, hipStream_t s);
-hipError_t launch_d_operand(GemmPrec prec, int r, int ld, const double *d2aa, const double *d2ab,
-                            const OperandRef &Daa, const OperandRef &Dab, hipStream_t s);
+// Packed pair indices over an r x r index square (row-major over the upper
+// triangle):  lt: i < j,  p = i (2r - i - 1)/2 + (j - i - 1),  r(r-1)/2 pairs;
+//             le: i <= j, p = i (2r - i + 1)/2 + (j - i),      r(r+1)/2 pairs.
+__host__ __device__ inline int npair_lt(int r) { return r * (r - 1) / 2; }
+__host__ __device__ inline int npair_le(int r) { return r * (r + 1) / 2; }
+__host__ __device__ inline int pair_lt(int r, int i, int j) { return i * (2 * r - i - 1) / 2 + (j - i - 1); }
+__host__ __device__ inline int pair_le(int r, int i, int j) { return i * (2 * r - i + 1) / 2 + (j - i); }
+__device__ inline void unpair_le(int r, int p, int &i, int &j) {
+  const double b = 2.0 * r + 1.0;
+  int ii = (int)((b - sqrt(b * b - 8.0 * p)) * 0.5);
+  if (ii < 0) ii = 0;
+  while (ii > 0 && ii * (2 * r - ii + 1) / 2 > p) --ii;
+  while ((ii + 1) * (2 * r - ii) / 2 <= p) ++ii;
+  i = ii;
+  j = ii + (p - ii * (2 * r - ii + 1) / 2);
+}
+// the lt pairs of r are the le pairs of r - 1 shifted by one column
+__device__ inline void unpair_lt(int r, int p, int &i, int &j) {
+  unpair_le(r - 1, p, i, j);
+  ++j;
+}
+// leading dimensions (K padded to the GEMM K pad) of the packed pp operands
+inline int64_t ld_pair_lt(int r) { return round_up(npair_lt(r), kKPad); }
+inline int64_t ld_pair_le(int r) { return round_up(npair_le(r), kKPad); }
+
+// Packed pp A operands D_aa, D_S, D_A (rows and K over pair indices).
+hipError_t launch_d_operand(GemmPrec prec, int r, const double *d2aa, const double *d2ab,
+                            const OperandRef &Daa, const OperandRef &DS, const OperandRef &DA,
+                            hipStream_t s);
 hipError_t launch_zero_kpad(GemmPrec prec, int r, int ld, const OperandRef &o, hipStream_t s);
 hipError_t launch_f(int r, const double *Aaa, const double *Aab, const double *g, double *part,
                     double *f, hipStream_t s);
 hipError_t launch_mode(GemmPrec prec, const ModeArgs &m, const OperandRef &out, hipStream_t s);
-hipError_t launch_g2(GemmPrec prec, int r, int ld, const double *Aaa, const double *Aab,
-                     const double *Haa, const double *Hab, const double *f, double *G2aa,
-                     double *G2ab, const OperandRef &Baa, const OperandRef &Bab, hipStream_t s);
+// G2 (natural FP64) and the packed pp B operands B_aa, B_S, B_A.
+hipError_t launch_g2(GemmPrec prec, int r, const double *Aaa, const double *Aab, const double *Haa,
+                     const double *Hab, const double *f, double *G2aa, double *G2ab,
+                     const OperandRef &Baa, const OperandRef &BS, const OperandRef &BA, hipStream_t s);
+// S from the packed pp products (Zaa [(i<j)][r^2], ZS [(i<=j)][r^2], ZA [(i<j)][r^2]),
+// the particle-hole products and the gamma-t terms.
 hipError_t launch_assemble(int r, const double *g, const double *t, const double *Zaa,
-                           const double *Zab, const double *Pp, const double *Pm, const double *E3,
-                           double *Saa, double *Sab, hipStream_t s);
+                           const double *ZS, const double *ZA, const double *Pp, const double *Pm,
+                           const double *E3, double *Saa, double *Sab, hipStream_t s);
 struct ActiveBits { uint64_t w[4]; };  // per-orbital active flags, r <= 256
 hipError_t launch_finish(int r, double sigma, const double *Saa, const double *Sab,
                          const double *Caa, const double *Cab, double *Oaa, double *Oab,

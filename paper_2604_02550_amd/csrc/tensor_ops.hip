@@ -122,19 +122,53 @@ __global__ void k_w_ph(int r, int ld, const double *__restrict__ g, const double
   R3.put(e, w_ab(d2ab, g, r, j, p, s, l));
 }
 
-// pp A operands: the unnormalised 2-RDM blocks Gamma2 = 2 2D (the factor 2
-// is applied as the GEMM alpha), copied into the padded operand layout.
+// pp A operands, packed by the pair symmetries of the 2-RDM blocks (the factor
+// of the unnormalised Gamma2 = 2 2D and the 2 of the exchange are GEMM alphas):
+//   D_aa[(i<j), (r<s)] = d2aa[i,j,r,s]                       (antisymmetric pairs)
+//   D_S [(i<=j), (r<=s)] = d2ab[i,j,r,s] + d2ab[i,j,s,r]  (r < s),  d2ab[i,j,r,r]
+//   D_A [(i<j), (r<s)]  = d2ab[i,j,r,s] - d2ab[i,j,s,r]
+// One block per unordered pair i <= j stages the two 2-RDM rows in LDS; the
+// K padding of each written row is zeroed.
 template <class O>
-__global__ void k_d_operand(int r, int ld, const double *__restrict__ d2aa,
-                            const double *__restrict__ d2ab, O Daa, O Dab) {
-  const int64_t r2 = (int64_t)r * r;
-  const int64_t e = gtid();
-  if (e >= r2 * ld) return;
-  const int col = e % ld;
-  const int64_t row = e / ld;
-  if (col >= r2) { Daa.put(e, 0.0); Dab.put(e, 0.0); return; }
-  Daa.put(e, d2aa[row * r2 + col]);
-  Dab.put(e, d2ab[row * r2 + col]);
+__global__ void __launch_bounds__(256)
+k_d_operand(int r, int ld_lt, int ld_le, const double *__restrict__ d2aa,
+            const double *__restrict__ d2ab, O Daa, O DS, O DA) {
+  extern __shared__ double dop_smem[];
+  const int r2 = r * r;
+  int i, j;
+  unpair_le(r, blockIdx.x, i, j);
+  const int64_t src = ((int64_t)i * r + j) * r2;
+  double *ra = dop_smem, *rb = dop_smem + r2;
+  for (int e = threadIdx.x; e < r2; e += 256) {
+    ra[e] = d2aa[src + e];
+    rb[e] = d2ab[src + e];
+  }
+  __syncthreads();
+  const int nle = npair_le(r), nlt = npair_lt(r);
+  const int64_t rowS = (int64_t)blockIdx.x * ld_le;
+  for (int q = threadIdx.x; q < ld_le; q += 256) {
+    double v = 0.0;
+    if (q < nle) {
+      int a, b;
+      unpair_le(r, q, a, b);
+      v = a == b ? rb[a * r + a] : rb[a * r + b] + rb[b * r + a];
+    }
+    DS.put(rowS + q, v);
+  }
+  if (i < j) {
+    const int64_t rowA = (int64_t)pair_lt(r, i, j) * ld_lt;
+    for (int q = threadIdx.x; q < ld_lt; q += 256) {
+      double va = 0.0, vd = 0.0;
+      if (q < nlt) {
+        int a, b;
+        unpair_lt(r, q, a, b);
+        va = ra[a * r + b];
+        vd = rb[a * r + b] - rb[b * r + a];
+      }
+      Daa.put(rowA + q, va);
+      DA.put(rowA + q, vd);
+    }
+  }
 }
 
 // Zero the K-padding columns [r^2, ld) of rows [0, r^2) of an operand whose
@@ -349,37 +383,65 @@ k_mode(ModeArgs m, O out, int npanels) {
 }
 
 // ---------------------------------------------------------------------------
-// pp B operands and the G2 tensors (fold of the f and H terms):
+// G2 tensors (fold of the f and H terms) and the packed pp B operands:
 //   G2_aa[k,l,r,s] = H_aa[k,l,r,s] - H_aa[l,k,r,s]
 //                    + f[k,r] d_ls - f[k,s] d_lr - f[l,r] d_ks + f[l,s] d_kr
 //   G2_ab[k,l,r,s] = H_ab[k,l,r,s] + H_ab[l,k,s,r] + f[k,r] d_ls + f[l,s] d_kr
-//   Bpp = A - G2 (operand precision, padded), G2 kept in FP64.
+//   B = A - G2 per block (FP64); G2 kept in FP64 (natural layout).
+// Operand rows (k,l), K packed to match the D operands:
+//   B_aa[(k,l), (r<s)] = B_aa[k,l,r,s] - B_aa[k,l,s,r]
+//   B_S [(k,l), (r<=s)] = B_ab[k,l,r,s] + B_ab[k,l,s,r]
+//   B_A [(k,l), (r<s)] = B_ab[k,l,r,s] - B_ab[k,l,s,r]
+// One block per row (k,l): the natural B rows are staged in LDS.
 // ---------------------------------------------------------------------------
 template <class O>
-__global__ void k_g2(int r, int ld, const double *__restrict__ Aaa, const double *__restrict__ Aab,
-                     const double *__restrict__ Haa, const double *__restrict__ Hab,
-                     const double *__restrict__ f, double *__restrict__ G2aa,
-                     double *__restrict__ G2ab, O Baa, O Bab) {
-  const int64_t r2 = (int64_t)r * r;
-  const int64_t e = gtid();
-  if (e >= r2 * ld) return;
-  const int col = e % ld;
-  const int row = e / ld;
-  if (col >= r2) { Baa.put(e, 0.0); Bab.put(e, 0.0); return; }
-  const int k = row / r, l = row % r, rr = col / r, s = col % r;
-  const int64_t nat = (int64_t)row * r2 + col;
-  double gaa = Haa[nat] - Haa[((int64_t)l * r + k) * r2 + col];
-  if (l == s) gaa += f[k * r + rr];
-  if (l == rr) gaa -= f[k * r + s];
-  if (k == s) gaa -= f[l * r + rr];
-  if (k == rr) gaa += f[l * r + s];
-  double gab = Hab[nat] + Hab[((int64_t)l * r + k) * r2 + (int64_t)s * r + rr];
-  if (l == s) gab += f[k * r + rr];
-  if (k == rr) gab += f[l * r + s];
-  G2aa[nat] = gaa;
-  G2ab[nat] = gab;
-  Baa.put(e, Aaa[nat] - gaa);
-  Bab.put(e, Aab[nat] - gab);
+__global__ void __launch_bounds__(256)
+k_g2(int r, int ld_lt, int ld_le, const double *__restrict__ Aaa, const double *__restrict__ Aab,
+     const double *__restrict__ Haa, const double *__restrict__ Hab, const double *__restrict__ f,
+     double *__restrict__ G2aa, double *__restrict__ G2ab, O Baa, O BS, O BA) {
+  extern __shared__ double g2_smem[];
+  const int r2 = r * r;
+  const int row = blockIdx.x;
+  const int k = row / r, l = row - (row / r) * r;
+  const int64_t nat0 = (int64_t)row * r2, mir0 = ((int64_t)l * r + k) * r2;
+  double *ba = g2_smem, *bb = g2_smem + r2;
+  for (int e = threadIdx.x; e < r2; e += 256) {
+    const int rr = e / r, s = e - (e / r) * r;
+    double gaa = Haa[nat0 + e] - Haa[mir0 + e];
+    if (l == s) gaa += f[k * r + rr];
+    if (l == rr) gaa -= f[k * r + s];
+    if (k == s) gaa -= f[l * r + rr];
+    if (k == rr) gaa += f[l * r + s];
+    double gab = Hab[nat0 + e] + Hab[mir0 + (int64_t)s * r + rr];
+    if (l == s) gab += f[k * r + rr];
+    if (k == rr) gab += f[l * r + s];
+    G2aa[nat0 + e] = gaa;
+    G2ab[nat0 + e] = gab;
+    ba[e] = Aaa[nat0 + e] - gaa;
+    bb[e] = Aab[nat0 + e] - gab;
+  }
+  __syncthreads();
+  const int nle = npair_le(r), nlt = npair_lt(r);
+  for (int q = threadIdx.x; q < ld_le; q += 256) {
+    double v = 0.0;
+    if (q < nle) {
+      int a, b;
+      unpair_le(r, q, a, b);
+      v = bb[a * r + b] + bb[b * r + a];
+    }
+    BS.put((int64_t)row * ld_le + q, v);
+  }
+  for (int q = threadIdx.x; q < ld_lt; q += 256) {
+    double va = 0.0, vb = 0.0;
+    if (q < nlt) {
+      int a, b;
+      unpair_lt(r, q, a, b);
+      va = ba[a * r + b] - ba[b * r + a];
+      vb = bb[a * r + b] - bb[b * r + a];
+    }
+    Baa.put((int64_t)row * ld_lt + q, va);
+    BA.put((int64_t)row * ld_lt + q, vb);
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -388,7 +450,9 @@ __global__ void k_g2(int r, int ld, const double *__restrict__ Aaa, const double
 //               - (E1[i,j,k,l] - E1[j,i,k,l] - E1[i,j,l,k] + E1[j,i,l,k])
 //   S_ab = Z_ab + g_jl t_ik + g_ik t_jl
 //               - (E2[i,j,k,l] + E2[j,i,l,k] - E3[i,j,k,l] - E3[j,i,l,k])
-// with E1 = P+ + P-, E2 = P+ - P- (all stored [i,j,k,l]).
+// with E1 = P+ + P-, E2 = P+ - P- (all stored [i,j,k,l]).  The pp products
+// come packed: Z_aa = +-Zp_aa[(i<j)] (0 on i = j), and
+// Z_ab[i,j] = 1/2 (Z_S[(i<=j)] +- Z_A[(i<j)]) (sign + for i < j).
 // One block per unordered pair {i <= j} writes the slabs S[i,j,:,:] and
 // S[j,i,:,:]; for a chunk of kKC values of k it stages, for both slabs (i,j)
 // and (j,i) of P+, P- and E3, the rows X[.,.,k,:] and the column stripes
@@ -398,7 +462,7 @@ constexpr int kKC = 8;
 
 __global__ void __launch_bounds__(256)
 k_assemble(int r, const double *__restrict__ g, const double *__restrict__ t,
-           const double *__restrict__ Zaa, const double *__restrict__ Zab,
+           const double *__restrict__ Zaa, const double *__restrict__ ZS, const double *__restrict__ ZA,
            const double *__restrict__ Pp, const double *__restrict__ Pm,
            const double *__restrict__ E3, double *__restrict__ Saa, double *__restrict__ Sab) {
   extern __shared__ double asm_smem[];
@@ -408,6 +472,8 @@ k_assemble(int r, const double *__restrict__ g, const double *__restrict__ t,
   const int j = i + rem;
   const int64_t r2 = (int64_t)r * r;
   const double *X[3] = {Pp, Pm, E3};
+  const int64_t zs0 = (int64_t)blockIdx.x * r2;                        // Z_S row (i<=j)
+  const int64_t za0 = i < j ? (int64_t)pair_lt(r, i, j) * r2 : 0;      // Z_aa, Z_A row (i<j)
   const int64_t slab[2] = {((int64_t)i * r + j) * r2, ((int64_t)j * r + i) * r2};
   // rowp[s][x][kk][l] and colp[s][x][l][kk] (padded)
   const int RW = kKC * r, CW = r * (kKC + 1);
@@ -456,8 +522,12 @@ k_assemble(int r, const double *__restrict__ g, const double *__restrict__ t,
                            g[a * r + k] * t[b * r + l] + g[b * r + k] * t[a * r + l];
       const double gt_ab = g[b * r + l] * t[a * r + k] + g[a * r + k] * t[b * r + l];
       const int64_t out = slab[s] + (int64_t)k * r + l;
-      Saa[out] = Zaa[out] - gt_aa - e1;
-      Sab[out] = Zab[out] + gt_ab - e2;
+      const int64_t kl = (int64_t)k * r + l;
+      const double sg = i == j ? 0.0 : (s ? -1.0 : 1.0);
+      const double zaa = sg * Zaa[za0 + kl];
+      const double zab = 0.5 * (ZS[zs0 + kl] + sg * ZA[za0 + kl]);
+      Saa[out] = zaa - gt_aa - e1;
+      Sab[out] = zab + gt_ab - e2;
     }
     __syncthreads();
   }
@@ -779,11 +849,18 @@ hipError_t launch_w_ph(GemmPrec prec, int r, int ld, const double *g, const doub
   return hipGetLastError();
 }
 
-hipError_t launch_d_operand(GemmPrec prec, int r, int ld, const double *d2aa, const double *d2ab,
-                            const OperandRef &Daa, const OperandRef &Dab, hipStream_t s) {
-  const int64_t n = (int64_t)r * r * ld;
-  ACSE_DISPATCH_OUT(prec, hipLaunchKernelGGL((k_d_operand<O>), grid_for(n), dim3(256), 0, s, r, ld,
-                                             d2aa, d2ab, make_out<O>(Daa), make_out<O>(Dab)));
+hipError_t launch_d_operand(GemmPrec prec, int r, const double *d2aa, const double *d2ab,
+                            const OperandRef &Daa, const OperandRef &DS, const OperandRef &DA,
+                            hipStream_t s) {
+  const size_t lds = (size_t)2 * r * r * sizeof(double);
+  const int ld_lt = (int)ld_pair_lt(r), ld_le = (int)ld_pair_le(r);
+  ACSE_DISPATCH_OUT(prec, {
+    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(&k_d_operand<O>),
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL((k_d_operand<O>), dim3((unsigned)npair_le(r)), dim3(256), lds, s, r, ld_lt, ld_le,
+                       d2aa, d2ab, make_out<O>(Daa), make_out<O>(DS), make_out<O>(DA));
+  });
   return hipGetLastError();
 }
 
@@ -851,24 +928,30 @@ hipError_t launch_mode(GemmPrec prec, const ModeArgs &m, const OperandRef &out, 
   return hipSuccess;
 }
 
-hipError_t launch_g2(GemmPrec prec, int r, int ld, const double *Aaa, const double *Aab,
-                     const double *Haa, const double *Hab, const double *f, double *G2aa,
-                     double *G2ab, const OperandRef &Baa, const OperandRef &Bab, hipStream_t s) {
-  const int64_t n = (int64_t)r * r * ld;
-  ACSE_DISPATCH_OUT(prec, hipLaunchKernelGGL((k_g2<O>), grid_for(n), dim3(256), 0, s, r, ld, Aaa, Aab,
-                                             Haa, Hab, f, G2aa, G2ab, make_out<O>(Baa), make_out<O>(Bab)));
+hipError_t launch_g2(GemmPrec prec, int r, const double *Aaa, const double *Aab, const double *Haa,
+                     const double *Hab, const double *f, double *G2aa, double *G2ab,
+                     const OperandRef &Baa, const OperandRef &BS, const OperandRef &BA, hipStream_t s) {
+  const size_t lds = (size_t)2 * r * r * sizeof(double);
+  const int ld_lt = (int)ld_pair_lt(r), ld_le = (int)ld_pair_le(r);
+  ACSE_DISPATCH_OUT(prec, {
+    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(&k_g2<O>),
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL((k_g2<O>), dim3((unsigned)(r * r)), dim3(256), lds, s, r, ld_lt, ld_le, Aaa, Aab,
+                       Haa, Hab, f, G2aa, G2ab, make_out<O>(Baa), make_out<O>(BS), make_out<O>(BA));
+  });
   return hipGetLastError();
 }
 
 hipError_t launch_assemble(int r, const double *g, const double *t, const double *Zaa,
-                           const double *Zab, const double *Pp, const double *Pm, const double *E3,
-                           double *Saa, double *Sab, hipStream_t s) {
+                           const double *ZS, const double *ZA, const double *Pp, const double *Pm,
+                           const double *E3, double *Saa, double *Sab, hipStream_t s) {
   const size_t lds = (size_t)6 * (kKC * r + r * (kKC + 1)) * sizeof(double);
   hipError_t err = hipFuncSetAttribute(reinterpret_cast<const void *>(&k_assemble),
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   if (err != hipSuccess) return err;
   const unsigned npairs = (unsigned)(r * (r + 1) / 2);
-  hipLaunchKernelGGL(k_assemble, dim3(npairs), dim3(256), lds, s, r, g, t, Zaa, Zab, Pp, Pm, E3, Saa,
+  hipLaunchKernelGGL(k_assemble, dim3(npairs), dim3(256), lds, s, r, g, t, Zaa, ZS, ZA, Pp, Pm, E3, Saa,
                      Sab);
   return hipGetLastError();
 }
