@@ -70,6 +70,9 @@ struct acse_ctx_s {
   void *bbase = nullptr;
   int64_t bbytes = 0;
   std::map<std::string, int> tuned_batch;  // "prec:r1,r2,..." -> tile configuration
+  // side streams (default priority) for the per-instance stages of a batch
+  hipStream_t side[4] = {};
+  hipEvent_t fork_ev = nullptr, join_ev[4] = {};
   GemmProb *hdesc = nullptr;    // pinned staging of the persistent GEMM descriptors
   int hdesc_cap = 0;
   hipEvent_t hdesc_done = nullptr;  // recorded after the staging copy
@@ -463,6 +466,11 @@ acse_status acse_destroy(acse_ctx ctx) {
   if (ctx->bbase) (void)hipFree(ctx->bbase);
   if (ctx->hdesc) (void)hipHostFree(ctx->hdesc);
   if (ctx->hdesc_done) (void)hipEventDestroy(ctx->hdesc_done);
+  for (int q = 0; q < 4; ++q) {
+    if (ctx->side[q]) (void)hipStreamDestroy(ctx->side[q]);
+    if (ctx->join_ev[q]) (void)hipEventDestroy(ctx->join_ev[q]);
+  }
+  if (ctx->fork_ev) (void)hipEventDestroy(ctx->fork_ev);
   (void)hipFree(ctx->base);
   delete ctx;
   return ACSE_OK;
@@ -1005,6 +1013,7 @@ extern "C" acse_status acse_energy_vjp(acse_ctx ctx, const acse_problem *prob, d
 namespace {
 
 constexpr int kMaxBatch = 4096;
+constexpr int kBatchStreams = 4;  // side streams for the per-instance stages
 
 struct BatchPlan {
   std::vector<Workspace> ws;
@@ -1070,6 +1079,11 @@ acse_status ensure_batch(acse_ctx c, int count, const acse_problem *probs, Batch
     c->hdesc_cap = kProbsPerMap * count;
   }
   if (!c->hdesc_done) HIP_TRY(c, hipEventCreateWithFlags(&c->hdesc_done, hipEventDisableTiming));
+  if (!c->fork_ev) HIP_TRY(c, hipEventCreateWithFlags(&c->fork_ev, hipEventDisableTiming));
+  for (int q = 0; q < kBatchStreams; ++q) {
+    if (!c->side[q]) HIP_TRY(c, hipStreamCreateWithFlags(&c->side[q], hipStreamNonBlocking));
+    if (!c->join_ev[q]) HIP_TRY(c, hipEventCreateWithFlags(&c->join_ev[q], hipEventDisableTiming));
+  }
   char *base = static_cast<char *>(c->bbase);
   plan.ws.assign(count, Workspace{});
   for (int i = 0; i < count; ++i) carve(base + off[i], probs[i].r, false, plan.ws[i]);
@@ -1087,21 +1101,72 @@ int batch_cfg(acse_ctx c, GemmPrec prec, int count, const acse_problem *probs, i
   return gemm_default_cfg(prec, (int)(rmax * rmax), (int)(rmax * rmax));
 }
 
+// Routes the library's launches to another stream for a scope.
+struct StreamSwap {
+  acse_ctx c;
+  hipStream_t saved;
+  StreamSwap(acse_ctx c_, hipStream_t to) : c(c_), saved(c_->stream) { c->stream = to; }
+  ~StreamSwap() { c->stream = saved; }
+};
+
+// The side streams wait for everything enqueued so far on the context stream.
+acse_status fork_sides(acse_ctx c, int ns) {
+  HIP_TRY(c, hipEventRecord(c->fork_ev, c->stream));
+  for (int q = 0; q < ns; ++q) HIP_TRY(c, hipStreamWaitEvent(c->side[q], c->fork_ev, 0));
+  return ACSE_OK;
+}
+// The context stream waits for everything enqueued so far on the side streams.
+acse_status join_sides(acse_ctx c, int ns) {
+  for (int q = 0; q < ns; ++q) {
+    HIP_TRY(c, hipEventRecord(c->join_ev[q], c->side[q]));
+    HIP_TRY(c, hipStreamWaitEvent(c->stream, c->join_ev[q], 0));
+  }
+  return ACSE_OK;
+}
+
+// Per-instance stages run concurrently on the side streams (largest instances
+// first, each to the least loaded stream); the products of all instances run
+// as one persistent launch on the context stream in between.
 acse_status run_batched(acse_ctx c, int count, const acse_problem *probs, GemmPrec prec, int cfg,
                         double *const *Raa, double *const *Rab, BatchPlan &plan) {
   acse_status st;
+  const int ns = std::min(count, kBatchStreams);
+  std::vector<int> order(count), lane(count);
+  for (int i = 0; i < count; ++i) order[i] = i;
+  std::stable_sort(order.begin(), order.end(),
+                   [&](int a, int b) { return probs[a].r > probs[b].r; });
+  double load[kBatchStreams] = {};
+  for (int i : order) {
+    int best = 0;
+    for (int q = 1; q < ns; ++q)
+      if (load[q] < load[best]) best = q;
+    lane[i] = best;
+    const double rr = probs[i].r;
+    load[best] += rr * rr * rr * rr * rr;
+  }
   std::vector<GemmProb> gp(kProbsPerMap * (size_t)count);
-  for (int i = 0; i < count; ++i) {
+  if ((st = fork_sides(c, ns)) != ACSE_OK) return st;
+  // a failing launch still rejoins the side streams before returning
+  auto front = [&](int i) -> acse_status {
     const acse_problem *p = &probs[i];
     Workspace &w = plan.ws[i];
-    if ((st = prep_rdm_operands(c, p, prec, w)) != ACSE_OK) return st;
+    StreamSwap sw(c, c->side[lane[i]]);
+    acse_status s2 = prep_rdm_operands(c, p, prec, w);
+    if (s2 != ACSE_OK) return s2;
     {
       StageTimer t1(c, 1);
       HIP_TRY(c, launch_fold(p->r, p->n_alpha + p->n_beta, p->h, p->V, w.Aaa, w.Aab, c->stream));
     }
-    if ((st = map_front(c, p, prec, w.Aaa, w.Aab, w)) != ACSE_OK) return st;
+    if ((s2 = map_front(c, p, prec, w.Aaa, w.Aab, w)) != ACSE_OK) return s2;
     map_probs(w, prec, p->r, &gp[kProbsPerMap * (size_t)i]);
-  }
+    return ACSE_OK;
+  };
+  for (int i : order)
+    if ((st = front(i)) != ACSE_OK) {
+      (void)join_sides(c, ns);
+      return st;
+    }
+  if ((st = join_sides(c, ns)) != ACSE_OK) return st;
   {
     // the pinned staging buffer may still feed the previous call's copy
     HIP_TRY(c, hipEventSynchronize(c->hdesc_done));
@@ -1109,13 +1174,17 @@ acse_status run_batched(acse_ctx c, int count, const acse_problem *probs, GemmPr
     HIP_TRY(c, gemm_launch_persistent(prec, cfg, gp, c->hdesc, plan.dprobs, c->stream));
     HIP_TRY(c, hipEventRecord(c->hdesc_done, c->stream));
   }
+  if ((st = fork_sides(c, ns)) != ACSE_OK) return st;
   const ActiveBits none{};
-  for (int i = 0; i < count; ++i)
+  for (int i : order) {
+    StreamSwap sw(c, c->side[lane[i]]);
     if ((st = map_back(c, &probs[i], -1.0, Raa ? Raa[i] : plan.ws[i].Raa,
                        Rab ? Rab[i] : plan.ws[i].Rab, none, nullptr, nullptr, plan.norms + i,
                        plan.ws[i])) != ACSE_OK)
-      return st;
-  return ACSE_OK;
+      break;
+  }
+  const acse_status sj = join_sides(c, ns);
+  return st != ACSE_OK ? st : sj;
 }
 
 }  // namespace

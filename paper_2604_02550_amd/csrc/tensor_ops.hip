@@ -613,90 +613,109 @@ k_reduce_sum(int64_t n, const double *__restrict__ part, double *__restrict__ ou
 }
 
 // ---------------------------------------------------------------------------
-// t[j,k] = sum_x (W_aa[j,x] A_aa[k,x] + 2 W_ab[j,x] A_ab[k,x]),  x = (p,r,s) in [0, r^3).
-// Block b reduces its own x range; each thread owns up to 3 register tiles of
-// 4 x 4 (j,k) outputs; x slabs of kTChunk are staged x-major in LDS so a
-// thread reads its 4 j's and 4 k's as consecutive doubles.
+// Gram products  out[j,k] = sum_x (w1 P1[j,x] Q1[k,x] + w2 P2[j,x] Q2[k,x]),
+// x in [0, r^3) (for t: P = W, Q = A, weights 1 and 2).  A K-split over
+// kTBlocks blocks, each reducing its x range into an r x r partial on the FP64
+// MFMA: x slabs of kTChunk are staged row-wise in LDS (rows j >= r zero, the
+// weights folded into the P rows) and wave w owns the 16-row output blocks
+// NBW w ... NBW w + NBW - 1 against every 16-column block.
 // ---------------------------------------------------------------------------
 constexpr int kTChunk = 32;
 constexpr int kTBlocks = 512;
+constexpr int kTLdx = kTChunk + 1;  // odd LDS row stride
 
+template <int NBW>
 __global__ void __launch_bounds__(256)
-k_t_partial(int r, const double *__restrict__ Waa, const double *__restrict__ Aaa,
-            const double *__restrict__ Wab, const double *__restrict__ Aab, double w1, double w2,
+k_t_partial(int r, const double *__restrict__ P1, const double *__restrict__ Q1,
+            const double *__restrict__ P2, const double *__restrict__ Q2, double w1, double w2,
             double *__restrict__ part) {
   extern __shared__ double t_smem[];
-  const int rp = (r + 3) & ~3;      // j / k extent covered by 4 x 4 tiles
-  const int ls = rp + 2;            // LDS row stride (= 2 mod 4 doubles: staging stores spread over banks)
-  double *sWa = t_smem, *sAa = sWa + kTChunk * ls, *sWb = sAa + kTChunk * ls, *sAb = sWb + kTChunk * ls;
+  constexpr int NBMAX = 4 * NBW;
+  const int nb = (r + 15) >> 4;
+  const int rows = nb * 16;
+  double *sP1 = t_smem, *sQ1 = sP1 + rows * kTLdx, *sP2 = sQ1 + rows * kTLdx, *sQ2 = sP2 + rows * kTLdx;
   const int64_t X = (int64_t)r * r * r;
   const int64_t per = (X + gridDim.x - 1) / gridDim.x;
   const int64_t x0 = (int64_t)blockIdx.x * per, x1 = min(X, x0 + per);
-  const int nb = rp / 4;
-  double acc[3][16];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int lr = lane & 15, lk = lane >> 4;
+  typedef double d4 __attribute__((ext_vector_type(4)));
+  d4 acc[NBW][NBMAX];
 #pragma unroll
-  for (int u = 0; u < 3; ++u)
+  for (int a = 0; a < NBW; ++a)
 #pragma unroll
-    for (int q = 0; q < 16; ++q) acc[u][q] = 0.0;
+    for (int b = 0; b < NBMAX; ++b) acc[a][b] = d4{0.0, 0.0, 0.0, 0.0};
+  const bool two = P2 != nullptr;
   for (int64_t xc = x0; xc < x1; xc += kTChunk) {
-    for (int base = 0; base < kTChunk * rp; base += 256 * 4) {
-      double v[4][4];
+    // stage rows [0, rows) x columns [xc, xc + kTChunk): 4 arrays
+    for (int e0 = 0; e0 < rows * kTChunk; e0 += 256 * kStage) {
+      double v[kStage][4];
 #pragma unroll
-      for (int u = 0; u < 4; ++u) {
-        const int e = base + u * 256 + threadIdx.x;
-        const int c = e % kTChunk, j = e / kTChunk;
-        const int64_t x = xc + c;
-        const bool ok = e < kTChunk * rp && (j < r) && (x < x1);
-        const int64_t o = (int64_t)j * X + x;
-        v[u][0] = ld_ok(Waa, o, ok);
-        v[u][1] = ld_ok(Aaa, o, ok);
-        v[u][2] = ld_ok(Wab, o, ok);
-        v[u][3] = ld_ok(Aab, o, ok);
+      for (int u = 0; u < kStage; ++u) {
+        const int e = e0 + u * 256 + tid;
+        const int j = e / kTChunk, c = e - (e / kTChunk) * kTChunk;
+        const bool ok = e < rows * kTChunk && j < r && xc + c < x1;
+        const int64_t o = (int64_t)j * X + xc + c;
+        v[u][0] = ld_ok(P1, o, ok);
+        v[u][1] = ld_ok(Q1, o, ok);
+        v[u][2] = two ? ld_ok(P2, o, ok) : 0.0;
+        v[u][3] = two ? ld_ok(Q2, o, ok) : 0.0;
         if (!ok) v[u][0] = v[u][1] = v[u][2] = v[u][3] = 0.0;
       }
 #pragma unroll
-      for (int u = 0; u < 4; ++u) {
-        const int e = base + u * 256 + threadIdx.x;
-        if (e >= kTChunk * rp) continue;
-        const int c = e % kTChunk, j = e / kTChunk;
-        sWa[c * ls + j] = v[u][0];
-        sAa[c * ls + j] = v[u][1];
-        sWb[c * ls + j] = v[u][2];
-        sAb[c * ls + j] = v[u][3];
+      for (int u = 0; u < kStage; ++u) {
+        const int e = e0 + u * 256 + tid;
+        if (e >= rows * kTChunk) break;
+        const int j = e / kTChunk, c = e - (e / kTChunk) * kTChunk;
+        sP1[j * kTLdx + c] = w1 * v[u][0];
+        sQ1[j * kTLdx + c] = v[u][1];
+        sP2[j * kTLdx + c] = w2 * v[u][2];
+        sQ2[j * kTLdx + c] = v[u][3];
       }
     }
     __syncthreads();
 #pragma unroll
-    for (int u = 0; u < 3; ++u) {
-      const int q = threadIdx.x + u * 256;
-      if (q >= nb * nb) break;
-      const int jb = (q / nb) * 4, kb = (q % nb) * 4;
-      for (int c = 0; c < kTChunk; ++c) {
-        double wa[4], aa[4], wb[4], ab[4];
+    for (int st = 0; st < kTChunk / 4; ++st) {
+      const int col = st * 4 + lk;
+      double b1[NBMAX], b2[NBMAX];
 #pragma unroll
-        for (int v = 0; v < 4; ++v) {
-          wa[v] = sWa[c * ls + jb + v]; aa[v] = sAa[c * ls + kb + v];
-          wb[v] = sWb[c * ls + jb + v]; ab[v] = sAb[c * ls + kb + v];
+      for (int kb = 0; kb < NBMAX; ++kb) {
+        const int row = kb < nb ? kb * 16 + lr : 0;
+        b1[kb] = sQ1[row * kTLdx + col];
+        b2[kb] = sQ2[row * kTLdx + col];
+      }
+#pragma unroll
+      for (int a = 0; a < NBW; ++a) {
+        const int jb = wave * NBW + a;
+        if (jb >= nb) break;
+        const double a1 = sP1[(jb * 16 + lr) * kTLdx + col];
+        const double a2 = sP2[(jb * 16 + lr) * kTLdx + col];
+#pragma unroll
+        for (int kb = 0; kb < NBMAX; ++kb) {
+          if (kb >= nb) break;
+          acc[a][kb] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b1[kb], acc[a][kb], 0, 0, 0);
+          acc[a][kb] = __builtin_amdgcn_mfma_f64_16x16x4f64(a2, b2[kb], acc[a][kb], 0, 0, 0);
         }
-#pragma unroll
-        for (int a = 0; a < 4; ++a)
-#pragma unroll
-          for (int b = 0; b < 4; ++b) acc[u][a * 4 + b] += w1 * wa[a] * aa[b] + w2 * wb[a] * ab[b];
       }
     }
     __syncthreads();
   }
+  // accumulator item v of lane l: row lk + 4v, column lr of the 16 x 16 block
+  double *out = part + (int64_t)blockIdx.x * r * r;
 #pragma unroll
-  for (int u = 0; u < 3; ++u) {
-    const int q = threadIdx.x + u * 256;
-    if (q >= nb * nb) break;
-    const int jb = (q / nb) * 4, kb = (q % nb) * 4;
+  for (int a = 0; a < NBW; ++a) {
+    const int jb = wave * NBW + a;
+    if (jb >= nb) break;
 #pragma unroll
-    for (int a = 0; a < 4; ++a)
+    for (int kb = 0; kb < NBMAX; ++kb) {
+      if (kb >= nb) break;
+      const int k = kb * 16 + lr;
 #pragma unroll
-      for (int b = 0; b < 4; ++b)
-        if (jb + a < r && kb + b < r)
-          part[(int64_t)blockIdx.x * r * r + (jb + a) * r + kb + b] = acc[u][a * 4 + b];
+      for (int v = 0; v < 4; ++v) {
+        const int j = jb * 16 + lk + 4 * v;
+        if (j < r && k < r) out[j * r + k] = acc[a][kb][v];
+      }
+    }
   }
 }
 
@@ -985,13 +1004,22 @@ int t_partial_blocks() { return kTBlocks; }
 hipError_t launch_gram(int r, const double *P1, const double *Q1, double w1, const double *P2,
                        const double *Q2, double w2, double *part, double *out, int accumulate,
                        hipStream_t s) {
-  const int ls = ((r + 3) & ~3) + 2;
-  const size_t lds = (size_t)4 * kTChunk * ls * sizeof(double);
-  hipError_t err = hipFuncSetAttribute(reinterpret_cast<const void *>(&k_t_partial),
-                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-  if (err != hipSuccess) return err;
-  if (!P2) { P2 = P1; Q2 = Q1; w2 = 0.0; }
-  hipLaunchKernelGGL(k_t_partial, dim3(kTBlocks), dim3(256), lds, s, r, P1, Q1, P2, Q2, w1, w2, part);
+  const int rows = ((r + 15) / 16) * 16;
+  const size_t lds = (size_t)4 * rows * kTLdx * sizeof(double);
+  if (!P2) { Q2 = nullptr; w2 = 0.0; }
+  if (r <= 64) {
+    hipError_t err = hipFuncSetAttribute(reinterpret_cast<const void *>(&k_t_partial<1>),
+                                         hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (err != hipSuccess) return err;
+    hipLaunchKernelGGL((k_t_partial<1>), dim3(kTBlocks), dim3(256), lds, s, r, P1, Q1, P2, Q2, w1, w2,
+                       part);
+  } else {
+    hipError_t err = hipFuncSetAttribute(reinterpret_cast<const void *>(&k_t_partial<2>),
+                                         hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (err != hipSuccess) return err;
+    hipLaunchKernelGGL((k_t_partial<2>), dim3(kTBlocks), dim3(256), lds, s, r, P1, Q1, P2, Q2, w1, w2,
+                       part);
+  }
   return launch_t_reduce(r, kTBlocks, part, out, s, accumulate);
 }
 
