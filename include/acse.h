@@ -159,7 +159,7 @@ acse_status acse_energy_vjp(acse_ctx ctx, const acse_problem *prob, double Ebar,
  *   0  RDM-side operands (W = Gamma2 - 2/3 Gamma1^Gamma1 and its layouts)
  *   1  fold of the reduced Hamiltonian (Eq. (2))
  *   2  O(r^4)/O(r^5) transforms feeding the contractions
- *   3  grouped pair-index GEMM (the five O(r^6) contractions of one map)
+ *   3  grouped pair-index GEMM (the six O(r^6) contractions of one map)
  *   4  assembly, (ij)<->(kl) exchange and the FP64 norm
  *   5  step tail: axpy, trace restoration, 1-RDM contraction, energy
  * acse_profile_enable(ctx, 1) clears the totals and starts recording;
@@ -185,7 +185,7 @@ acse_status acse_autotune(acse_ctx ctx, const acse_problem *prob, const acse_opt
 /* Batched residual of Eq. (4) over `count` independent instances (1 <= count
  * <= 4096) of possibly different r, each r <= r_max: ground and excited
  * states, several molecules.  Per instance, the RDM operands, the fold and
- * the transforms run as in acse_residual.  The five pair-index products of
+ * the transforms run as in acse_residual.  The six pair-index products of
  * all instances then run in one persistent launch: a grid sized to the
  * resident capacity walks one tile list ordered by decreasing K.  The
  * per-instance assembly follows.

@@ -9,12 +9,15 @@
 //   f, t                 O(r^4), O(r^5) contractions of X with gamma and W
 //   H, G2, Bpp = A - G2  one-index transforms and the f terms (pp operand)
 //   Z_aa = Gamma2_aa Bpp_aa^T,  Z_ab = 2 Gamma2_ab Bpp_ab^T        pp GEMMs
+//     (packed over the pair symmetries of Gamma2: Z_aa on pairs i<j with K over
+//      r<s; Z_ab as its parts symmetric (i<=j, r<=s) and antisymmetric
+//      (i<j, r<s) under the pair exchange)
 //   P+- = (Xt_aa +- Xt_ab)(W'_a +- W'_b)^T,  E3 = -2 Xt3 W3^T      ph GEMMs
 //   C = 4/3 (gamma x gamma) G2 (separable, two one-index transforms)
 //   S = Z + C - gamma t terms - antisymmetrised particle-hole terms
 //   F = S - S^T (Hermitian X),  F = S + S^T (anti-Hermitian X)
 //
-// The five GEMMs (10 r^6 flops) run as one grouped MFMA launch.
+// The six products (about 7.5 r^6 flops) run as one grouped MFMA launch.
 #include <algorithm>
 #include <cmath>
 #include <cstdio>
