@@ -22,6 +22,12 @@
  *   d2ab[r^4]  2D(pa qb | ra sb) = 1/2 <a+_pa a+_qb a_sb a_ra>
  *              (the beta-beta block equals alpha-alpha; App. A traces
  *              Tr d2aa = Na(Na-1)/2, Tr d2ab = Na Nb/2).
+ *              Required symmetries (those of singlet RDMs, which the spin
+ *              blocks encode): d2aa antisymmetric within (p,q) and within
+ *              (r,s); d2ab[p,q,r,s] = d2ab[q,p,s,r] (the beta-alpha block is
+ *              the pair-exchanged alpha-beta block).  The contractions exploit
+ *              them; inputs without them give results for their symmetrised
+ *              parts, not an error.
  *   R_aa, R_ab the residual blocks R(ia ja | ka la), R(ia jb | ka lb), same layout.
  *   ||R||^2    the squared Frobenius norm over all spin-orbital elements,
  *              2 ||R_aa||^2 + 4 ||R_ab||^2, taken before the active mask.
