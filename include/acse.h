@@ -26,8 +26,8 @@
  *              blocks encode): d2aa antisymmetric within (p,q) and within
  *              (r,s); d2ab[p,q,r,s] = d2ab[q,p,s,r] (the beta-alpha block is
  *              the pair-exchanged alpha-beta block).  The contractions exploit
- *              them; inputs without them give results for their symmetrised
- *              parts, not an error.
+ *              them and do not check them: other inputs give results that
+ *              match no residual, with no error reported.
  *   R_aa, R_ab the residual blocks R(ia ja | ka la), R(ia jb | ka lb), same layout.
  *   ||R||^2    the squared Frobenius norm over all spin-orbital elements,
  *              2 ||R_aa||^2 + 4 ||R_ab||^2, taken before the active mask.
