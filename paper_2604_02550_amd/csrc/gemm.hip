@@ -21,15 +21,18 @@ typedef double d4 __attribute__((ext_vector_type(4)));
 typedef float f4 __attribute__((ext_vector_type(4)));
 typedef __bf16 bf8 __attribute__((ext_vector_type(8)));
 
+// PAD: LDS row padding in elements.  FP64/FP32 fragment reads take one element
+// per lane from 16 consecutive rows, so an odd row stride puts the 16 rows in
+// distinct banks (the staging stores then split into element-size pieces).
 struct TrF64 {
   using T = double;
   using Acc = d4;
-  static constexpr int NPLANE = 1, VEC = 2, PAD = 2, KSTEP = 4;
+  static constexpr int NPLANE = 1, VEC = 2, PAD = 1, KSTEP = 4;
 };
 struct TrF32 {
   using T = float;
   using Acc = f4;
-  static constexpr int NPLANE = 1, VEC = 4, PAD = 4, KSTEP = 4;
+  static constexpr int NPLANE = 1, VEC = 4, PAD = 1, KSTEP = 4;
 };
 struct TrBF16x3 {
   using T = __bf16;
@@ -115,6 +118,17 @@ __device__ __forceinline__ void gemm_tile(const GemmProb &P, int local) {
       }
     }
   };
+  // 16-byte chunk -> LDS at element offset o (whole-chunk store when the row
+  // stride keeps chunks 16-byte aligned, element stores otherwise)
+  auto put16 = [&](T *base, int o, const i4 &v) {
+    if constexpr ((LDK * sizeof(T)) % 16 == 0) {
+      *reinterpret_cast<i4 *>(base + o) = v;
+    } else {
+      const T *e = reinterpret_cast<const T *>(&v);
+#pragma unroll
+      for (int q = 0; q < VEC; ++q) base[o + q] = e[q];
+    }
+  };
   auto lstore = [&](int buf) {
 #pragma unroll
     for (int p = 0; p < NP; ++p) {
@@ -122,13 +136,13 @@ __device__ __forceinline__ void gemm_tile(const GemmProb &P, int local) {
       for (int c = 0; c < CH_A; ++c) {
         const int ch = tid + c * NT;
         const int row = ch / (BK / VEC), kc = (ch % (BK / VEC)) * VEC;
-        *reinterpret_cast<i4 *>(&As[buf][p][row * LDK + kc]) = ra[p][c];
+        put16(As[buf][p], row * LDK + kc, ra[p][c]);
       }
 #pragma unroll
       for (int c = 0; c < CH_B; ++c) {
         const int ch = tid + c * NT;
         const int row = ch / (BK / VEC), kc = (ch % (BK / VEC)) * VEC;
-        *reinterpret_cast<i4 *>(&Bs[buf][p][row * LDK + kc]) = rb[p][c];
+        put16(Bs[buf][p], row * LDK + kc, rb[p][c]);
       }
     }
   };
