@@ -453,8 +453,8 @@ k_g2(int r, int ld_lt, int ld_le, const double *__restrict__ Aaa, const double *
 // with E1 = P+ + P-, E2 = P+ - P- (all stored [i,j,k,l]).  The pp products
 // come packed: Z_aa = +-Zp_aa[(i<j)] (0 on i = j), and
 // Z_ab[i,j] = 1/2 (Z_S[(i<=j)] +- Z_A[(i<j)]) (sign + for i < j).
-// One block per unordered pair {i <= j} writes the slabs S[i,j,:,:] and
-// S[j,i,:,:]; for a chunk of kKC values of k it stages, for both slabs (i,j)
+// One block per unordered pair {i <= j} and chunk of kKC values of k writes
+// those rows of the slabs S[i,j,:,:] and S[j,i,:,:]; it stages, for both slabs (i,j)
 // and (j,i) of P+, P- and E3, the rows X[.,.,k,:] and the column stripes
 // X[.,.,:,k] in LDS, so every global read is a contiguous run.
 // ---------------------------------------------------------------------------
@@ -480,7 +480,8 @@ k_assemble(int r, const double *__restrict__ g, const double *__restrict__ t,
   double *rowp = asm_smem;
   double *colp = asm_smem + 6 * RW;
   const int nslab = (i == j) ? 1 : 2;
-  for (int k0 = 0; k0 < r; k0 += kKC) {
+  {
+    const int k0 = blockIdx.y * kKC;
     const int kc = min(kKC, r - k0);
     const int tot = 6 * kc * r;
     for (int base = 0; base < tot; base += 256 * kStage) {
@@ -534,9 +535,11 @@ k_assemble(int r, const double *__restrict__ g, const double *__restrict__ t,
 }
 
 // Out = S + sigma S^T ((ij)<->(kl)) with S = S' + C^T (C stored [k,l,i,j]),
-// on 32 x 32 tiles of the r^2 x r^2 pair matrix: the (row, col) tile and the
-// mirrored (col, row) tile of S' and C are both read row-wise into LDS.
-// Optional masked copy; per-block partial sums of 2 Out_aa^2 + 4 Out_ab^2.
+// on 32 x 32 tiles of the r^2 x r^2 pair matrix.  Out[b,a] = sigma Out[a,b],
+// so one block per tile pair (R0 <= C0) reads the (R0, C0) and (C0, R0) tiles
+// of S' and C once, writes the (R0, C0) tile and, transposed through LDS, the
+// mirrored one.  Optional masked copy (the mask is symmetric under the
+// exchange); per-block partial sums of 2 Out_aa^2 + 4 Out_ab^2.
 constexpr int kFT = 32;
 
 __global__ void __launch_bounds__(256)
@@ -547,8 +550,17 @@ k_finish(int r, double sigma, const double *__restrict__ Saa, const double *__re
   __shared__ double sA[kFT][kFT + 1], cA[kFT][kFT + 1], sB[kFT][kFT + 1], cB[kFT][kFT + 1];
   __shared__ double red[256];
   const int64_t r2 = (int64_t)r * r;
-  const int64_t R0 = (int64_t)blockIdx.y * kFT, C0 = (int64_t)blockIdx.x * kFT;
+  const int nt = (int)((r2 + kFT - 1) / kFT);
+  int tr, tc;
+  unpair_le(nt, blockIdx.x, tr, tc);
+  const int64_t R0 = (int64_t)tr * kFT, C0 = (int64_t)tc * kFT;
+  const bool diag = tr == tc;
   const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;  // 32 x 8
+  auto act = [&](int q2) { return (active.w[q2 >> 6] >> (q2 & 63)) & 1ull; };
+  auto masked = [&](int64_t row, int64_t col) {
+    const int i = (int)(row / r), j = (int)(row % r), k = (int)(col / r), l = (int)(col % r);
+    return act(i) && act(j) && act(k) && act(l);
+  };
   double acc = 0.0;
   for (int blk = 0; blk < 2; ++blk) {
     const double *S = blk ? Sab : Saa;
@@ -570,19 +582,37 @@ k_finish(int r, double sigma, const double *__restrict__ Saa, const double *__re
       cB[y][tx] = okb ? c2 : 0.0;
     }
     __syncthreads();
+    // the (R0, C0) tile: v = S[a,b] + C[b,a] + sigma (S[b,a] + C[a,b]); kept in sA
+    double v[kFT / 8];
 #pragma unroll
     for (int q = 0; q < kFT; q += 8) {
       const int y = ty + q;
+      v[q / 8] = (sA[y][tx] + cB[tx][y]) + sigma * (sB[tx][y] + cA[y][tx]);
+    }
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < kFT; q += 8) {
+      const int y = ty + q;
+      sA[y][tx] = v[q / 8];
       const int64_t row = R0 + y, col = C0 + tx;
       if (row < r2 && col < r2) {
-        const double v = (sA[y][tx] + cB[tx][y]) + sigma * (sB[tx][y] + cA[y][tx]);
         const int64_t e = row * r2 + col;
-        O[e] = v;
-        acc += w * v * v;
-        if (M) {
-          const int i = (int)(row / r), j = (int)(row % r), k = (int)(col / r), l = (int)(col % r);
-          auto act = [&](int q2) { return (active.w[q2 >> 6] >> (q2 & 63)) & 1ull; };
-          M[e] = (act(i) && act(j) && act(k) && act(l)) ? 0.0 : v;
+        O[e] = v[q / 8];
+        acc += (diag ? 1.0 : 2.0) * w * v[q / 8] * v[q / 8];
+        if (M) M[e] = masked(row, col) ? 0.0 : v[q / 8];
+      }
+    }
+    __syncthreads();
+    if (!diag) {
+#pragma unroll
+      for (int q = 0; q < kFT; q += 8) {
+        const int y = ty + q;
+        const int64_t row = C0 + y, col = R0 + tx;
+        if (row < r2 && col < r2) {
+          const double u = sigma * sA[tx][y];
+          const int64_t e = row * r2 + col;
+          O[e] = u;
+          if (M) M[e] = masked(row, col) ? 0.0 : u;
         }
       }
     }
@@ -590,11 +620,11 @@ k_finish(int r, double sigma, const double *__restrict__ Saa, const double *__re
   }
   red[threadIdx.x] = acc;
   __syncthreads();
-  for (int wv = 128; wv > 0; wv >>= 1) {
-    if (threadIdx.x < wv) red[threadIdx.x] += red[threadIdx.x + wv];
+  for (int w2 = 128; w2 > 0; w2 >>= 1) {
+    if (threadIdx.x < w2) red[threadIdx.x] += red[threadIdx.x + w2];
     __syncthreads();
   }
-  if (threadIdx.x == 0) partial[blockIdx.y * gridDim.x + blockIdx.x] = red[0];
+  if (threadIdx.x == 0) partial[blockIdx.x] = red[0];
 }
 
 // Sum of n partials in a fixed order by one block; writes out[0].
@@ -970,8 +1000,8 @@ hipError_t launch_assemble(int r, const double *g, const double *t, const double
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   if (err != hipSuccess) return err;
   const unsigned npairs = (unsigned)(r * (r + 1) / 2);
-  hipLaunchKernelGGL(k_assemble, dim3(npairs), dim3(256), lds, s, r, g, t, Zaa, ZS, ZA, Pp, Pm, E3, Saa,
-                     Sab);
+  hipLaunchKernelGGL(k_assemble, dim3(npairs, (unsigned)((r + kKC - 1) / kKC)), dim3(256), lds, s, r, g,
+                     t, Zaa, ZS, ZA, Pp, Pm, E3, Saa, Sab);
   return hipGetLastError();
 }
 
@@ -980,9 +1010,9 @@ hipError_t launch_finish(int r, double sigma, const double *Saa, const double *S
                          const ActiveBits &active, double *Maa, double *Mab, double *partial,
                          double *sum_out, hipStream_t s) {
   const int64_t nt = ((int64_t)r * r + kFT - 1) / kFT;
-  const int64_t nb = nt * nt;
-  hipLaunchKernelGGL(k_finish, dim3((unsigned)nt, (unsigned)nt), dim3(256), 0, s, r, sigma, Saa, Sab,
-                     Caa, Cab, Oaa, Oab, active, Maa, Mab, partial);
+  const int64_t nb = nt * (nt + 1) / 2;
+  hipLaunchKernelGGL(k_finish, dim3((unsigned)nb), dim3(256), 0, s, r, sigma, Saa, Sab, Caa, Cab, Oaa,
+                     Oab, active, Maa, Mab, partial);
   hipLaunchKernelGGL(k_reduce_sum, dim3(1), dim3(256), 0, s, nb, partial, sum_out);
   return hipGetLastError();
 }
