@@ -235,15 +235,16 @@ struct ModeShape {
   static constexpr int CB = COLS / 16;   // MFMA column blocks per panel
 };
 
-template <class O, int COLS, int NRB, bool HAS2>
+// KS: K steps of 4 (a compile-time trip count, 4 KS >= r; the A fragments and
+// panel rows beyond r are zero), so the MFMA chain is straight-line code.
+template <class O, int COLS, int NRB, bool HAS2, int KS>
 __global__ void __launch_bounds__(256)
 k_mode(ModeArgs m, O out, int npanels) {
   using S = ModeShape<COLS>;
-  constexpr int KSMAX = (16 * 4 * NRB) / 4;  // K steps of 4 for r <= 64 NRB
+  constexpr int KSMAX = KS;
   extern __shared__ double mode_smem[];
   const int r = m.r;
-  const int ks_n = (r + 3) >> 2;
-  double *T = mode_smem;  // [4 * ks_n][LDT] input panel; rows >= r stay zero
+  double *T = mode_smem;  // [4 KS][LDT] input panel; rows >= r stay zero
   const int tid = threadIdx.x;
   const int lane = tid & 63, wave = tid >> 6;
   const int lr = lane & 15, lk = lane >> 4;
@@ -265,7 +266,7 @@ k_mode(ModeArgs m, O out, int npanels) {
       afr[q][ks] = ok ? v : 0.0;
     }
   }
-  for (int e = r * S::LDT + tid; e < 4 * ks_n * S::LDT; e += 256) T[e] = 0.0;
+  for (int e = r * S::LDT + tid; e < 4 * KS * S::LDT; e += 256) T[e] = 0.0;
 
   // flat walk (Bn == 1): element f of the panel is column f / r, row f % r
   const int dc = 256 / r, dy = 256 - (256 / r) * r;
@@ -343,15 +344,13 @@ k_mode(ModeArgs m, O out, int npanels) {
       for (int cb = 0; cb < S::CB; ++cb) acc[q][cb] = mode_d4{0.0, 0.0, 0.0, 0.0};
 #pragma unroll
     for (int ks = 0; ks < KSMAX; ++ks) {
-      if (ks < ks_n) {
-        const double *tp = T + (ks * 4 + lk) * S::LDT + lr;
+      const double *tp = T + (ks * 4 + lk) * S::LDT + lr;
 #pragma unroll
-        for (int cb = 0; cb < S::CB; ++cb) {
-          const double bfr = tp[cb * 16];
+      for (int cb = 0; cb < S::CB; ++cb) {
+        const double bfr = tp[cb * 16];
 #pragma unroll
-          for (int q = 0; q < NRB; ++q)
-            acc[q][cb] = __builtin_amdgcn_mfma_f64_16x16x4f64(afr[q][ks], bfr, acc[q][cb], 0, 0, 0);
-        }
+        for (int q = 0; q < NRB; ++q)
+          acc[q][cb] = __builtin_amdgcn_mfma_f64_16x16x4f64(afr[q][ks], bfr, acc[q][cb], 0, 0, 0);
       }
     }
     // store: accumulator item v of lane l is row lk + 4v of the block, column lr
@@ -654,15 +653,16 @@ constexpr int kTChunk = 32;
 constexpr int kTBlocks = 512;
 constexpr int kTLdx = kTChunk + 1;  // odd LDS row stride
 
-template <int NBW>
+// NB = ceil(r / 16) output blocks per side (compile time, so the MFMA chains
+// are straight-line code); wave w owns block rows w and w + 4.
+template <int NB>
 __global__ void __launch_bounds__(256)
 k_t_partial(int r, const double *__restrict__ P1, const double *__restrict__ Q1,
             const double *__restrict__ P2, const double *__restrict__ Q2, double w1, double w2,
             double *__restrict__ part) {
   extern __shared__ double t_smem[];
-  constexpr int NBMAX = 4 * NBW;
-  const int nb = (r + 15) >> 4;
-  const int rows = nb * 16;
+  constexpr int rows = NB * 16;
+  constexpr int NBW = NB > 4 ? 2 : 1;
   double *sP1 = t_smem, *sQ1 = sP1 + rows * kTLdx, *sP2 = sQ1 + rows * kTLdx, *sQ2 = sP2 + rows * kTLdx;
   const int64_t X = (int64_t)r * r * r;
   const int64_t per = (X + gridDim.x - 1) / gridDim.x;
@@ -670,11 +670,11 @@ k_t_partial(int r, const double *__restrict__ P1, const double *__restrict__ Q1,
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int lr = lane & 15, lk = lane >> 4;
   typedef double d4 __attribute__((ext_vector_type(4)));
-  d4 acc[NBW][NBMAX];
+  d4 acc[NBW][NB];
 #pragma unroll
   for (int a = 0; a < NBW; ++a)
 #pragma unroll
-    for (int b = 0; b < NBMAX; ++b) acc[a][b] = d4{0.0, 0.0, 0.0, 0.0};
+    for (int b = 0; b < NB; ++b) acc[a][b] = d4{0.0, 0.0, 0.0, 0.0};
   const bool two = P2 != nullptr;
   for (int64_t xc = x0; xc < x1; xc += kTChunk) {
     // stage rows [0, rows) x columns [xc, xc + kTChunk): 4 arrays
@@ -704,41 +704,41 @@ k_t_partial(int r, const double *__restrict__ P1, const double *__restrict__ Q1,
       }
     }
     __syncthreads();
+    if (wave < NB) {
 #pragma unroll
-    for (int st = 0; st < kTChunk / 4; ++st) {
-      const int col = st * 4 + lk;
-      double b1[NBMAX], b2[NBMAX];
+      for (int st = 0; st < kTChunk / 4; ++st) {
+        const int col = st * 4 + lk;
+        double b1[NB], b2[NB];
 #pragma unroll
-      for (int kb = 0; kb < NBMAX; ++kb) {
-        const int row = kb < nb ? kb * 16 + lr : 0;
-        b1[kb] = sQ1[row * kTLdx + col];
-        b2[kb] = sQ2[row * kTLdx + col];
-      }
+        for (int kb = 0; kb < NB; ++kb) {
+          b1[kb] = sQ1[(kb * 16 + lr) * kTLdx + col];
+          b2[kb] = sQ2[(kb * 16 + lr) * kTLdx + col];
+        }
 #pragma unroll
-      for (int a = 0; a < NBW; ++a) {
-        const int jb = wave * NBW + a;
-        if (jb >= nb) break;
-        const double a1 = sP1[(jb * 16 + lr) * kTLdx + col];
-        const double a2 = sP2[(jb * 16 + lr) * kTLdx + col];
+        for (int a = 0; a < NBW; ++a) {
+          // NBW = 2 only for NB > 4: the second row block of wave w is w + 4 (< NB when w < NB - 4)
+          const int jb = wave + 4 * a < NB ? wave + 4 * a : wave;
+          const double a1 = sP1[(jb * 16 + lr) * kTLdx + col];
+          const double a2 = sP2[(jb * 16 + lr) * kTLdx + col];
 #pragma unroll
-        for (int kb = 0; kb < NBMAX; ++kb) {
-          if (kb >= nb) break;
-          acc[a][kb] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b1[kb], acc[a][kb], 0, 0, 0);
-          acc[a][kb] = __builtin_amdgcn_mfma_f64_16x16x4f64(a2, b2[kb], acc[a][kb], 0, 0, 0);
+          for (int kb = 0; kb < NB; ++kb) {
+            acc[a][kb] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b1[kb], acc[a][kb], 0, 0, 0);
+            acc[a][kb] = __builtin_amdgcn_mfma_f64_16x16x4f64(a2, b2[kb], acc[a][kb], 0, 0, 0);
+          }
         }
       }
     }
     __syncthreads();
   }
   // accumulator item v of lane l: row lk + 4v, column lr of the 16 x 16 block
+  if (wave >= NB) return;
   double *out = part + (int64_t)blockIdx.x * r * r;
 #pragma unroll
   for (int a = 0; a < NBW; ++a) {
-    const int jb = wave * NBW + a;
-    if (jb >= nb) break;
+    if (wave + 4 * a >= NB) break;
+    const int jb = wave + 4 * a;
 #pragma unroll
-    for (int kb = 0; kb < NBMAX; ++kb) {
-      if (kb >= nb) break;
+    for (int kb = 0; kb < NB; ++kb) {
       const int k = kb * 16 + lr;
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
@@ -931,20 +931,22 @@ hipError_t launch_f(int r, const double *Aaa, const double *Aab, const double *g
 
 // r <= 64: one 16-row block of M per wave, 32-column panels; r <= 96: two
 // row blocks per wave, 16-column panels (the prefetch stays at 8 per thread).
+// K steps rounded up to a multiple of 4 (at most 3 steps of zero padding).
 static int mode_cols(int r) { return r <= 64 ? 32 : 16; }
+static int mode_ks(int r) { return (((r + 3) / 4) + 3) / 4 * 4; }
 
 size_t mode_lds_bytes(int r) {
   const int ldt = mode_cols(r) + 1;
-  return (size_t)(4 * ((r + 3) / 4) * ldt) * sizeof(double);
+  return (size_t)(4 * mode_ks(r) * ldt) * sizeof(double);
 }
 
-template <class O, int COLS, int NRB, bool HAS2>
+template <class O, int COLS, int NRB, bool HAS2, int KS>
 static hipError_t launch_mode_t(const ModeArgs &m, O out, hipStream_t s) {
   static int resident[kModeMaxR + 1] = {};  // blocks the device holds at once, by r
   const size_t lds = mode_lds_bytes(m.r);
   int &res = resident[m.r];
   if (res == 0) {
-    const void *fn = reinterpret_cast<const void *>(&k_mode<O, COLS, NRB, HAS2>);
+    const void *fn = reinterpret_cast<const void *>(&k_mode<O, COLS, NRB, HAS2, KS>);
     int dev = 0, cus = 0, per_cu = 0;
     hipError_t e = hipGetDevice(&dev);
     if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
@@ -955,16 +957,26 @@ static hipError_t launch_mode_t(const ModeArgs &m, O out, hipStream_t s) {
   const int64_t ncols = m.A * m.Bn;
   const int npanels = (int)((ncols + COLS - 1) / COLS);
   if (npanels == 0) return hipSuccess;
-  hipLaunchKernelGGL((k_mode<O, COLS, NRB, HAS2>), dim3(std::min(npanels, res)), dim3(256), lds, s, m,
-                     out, npanels);
+  hipLaunchKernelGGL((k_mode<O, COLS, NRB, HAS2, KS>), dim3(std::min(npanels, res)), dim3(256), lds, s,
+                     m, out, npanels);
   return hipGetLastError();
+}
+
+template <class O, bool HAS2>
+static hipError_t launch_mode_h(const ModeArgs &m, O out, hipStream_t s) {
+  switch (mode_ks(m.r)) {
+    case 4: return launch_mode_t<O, 32, 1, HAS2, 4>(m, out, s);
+    case 8: return launch_mode_t<O, 32, 1, HAS2, 8>(m, out, s);
+    case 12: return launch_mode_t<O, 32, 1, HAS2, 12>(m, out, s);
+    case 16: return launch_mode_t<O, 32, 1, HAS2, 16>(m, out, s);
+    case 20: return launch_mode_t<O, 16, 2, HAS2, 20>(m, out, s);
+    default: return launch_mode_t<O, 16, 2, HAS2, 24>(m, out, s);
+  }
 }
 
 template <class O>
 static hipError_t launch_mode_o(const ModeArgs &m, O out, hipStream_t s) {
-  if (m.in2)
-    return m.r <= 64 ? launch_mode_t<O, 32, 1, true>(m, out, s) : launch_mode_t<O, 16, 2, true>(m, out, s);
-  return m.r <= 64 ? launch_mode_t<O, 32, 1, false>(m, out, s) : launch_mode_t<O, 16, 2, false>(m, out, s);
+  return m.in2 ? launch_mode_h<O, true>(m, out, s) : launch_mode_h<O, false>(m, out, s);
 }
 
 hipError_t launch_mode(GemmPrec prec, const ModeArgs &m, const OperandRef &out, hipStream_t s) {
@@ -1031,25 +1043,33 @@ hipError_t launch_t_reduce(int r, int nparts, const double *part, double *t, hip
 
 int t_partial_blocks() { return kTBlocks; }
 
+template <int NB>
+static hipError_t launch_gram_nb(int r, const double *P1, const double *Q1, double w1,
+                                 const double *P2, const double *Q2, double w2, double *part,
+                                 hipStream_t s) {
+  const size_t lds = (size_t)4 * NB * 16 * kTLdx * sizeof(double);
+  hipError_t err = hipFuncSetAttribute(reinterpret_cast<const void *>(&k_t_partial<NB>),
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  if (err != hipSuccess) return err;
+  hipLaunchKernelGGL((k_t_partial<NB>), dim3(kTBlocks), dim3(256), lds, s, r, P1, Q1, P2, Q2, w1, w2,
+                     part);
+  return hipGetLastError();
+}
+
 hipError_t launch_gram(int r, const double *P1, const double *Q1, double w1, const double *P2,
                        const double *Q2, double w2, double *part, double *out, int accumulate,
                        hipStream_t s) {
-  const int rows = ((r + 15) / 16) * 16;
-  const size_t lds = (size_t)4 * rows * kTLdx * sizeof(double);
   if (!P2) { Q2 = nullptr; w2 = 0.0; }
-  if (r <= 64) {
-    hipError_t err = hipFuncSetAttribute(reinterpret_cast<const void *>(&k_t_partial<1>),
-                                         hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-    if (err != hipSuccess) return err;
-    hipLaunchKernelGGL((k_t_partial<1>), dim3(kTBlocks), dim3(256), lds, s, r, P1, Q1, P2, Q2, w1, w2,
-                       part);
-  } else {
-    hipError_t err = hipFuncSetAttribute(reinterpret_cast<const void *>(&k_t_partial<2>),
-                                         hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-    if (err != hipSuccess) return err;
-    hipLaunchKernelGGL((k_t_partial<2>), dim3(kTBlocks), dim3(256), lds, s, r, P1, Q1, P2, Q2, w1, w2,
-                       part);
+  hipError_t err;
+  switch ((r + 15) / 16) {
+    case 1: err = launch_gram_nb<1>(r, P1, Q1, w1, P2, Q2, w2, part, s); break;
+    case 2: err = launch_gram_nb<2>(r, P1, Q1, w1, P2, Q2, w2, part, s); break;
+    case 3: err = launch_gram_nb<3>(r, P1, Q1, w1, P2, Q2, w2, part, s); break;
+    case 4: err = launch_gram_nb<4>(r, P1, Q1, w1, P2, Q2, w2, part, s); break;
+    case 5: err = launch_gram_nb<5>(r, P1, Q1, w1, P2, Q2, w2, part, s); break;
+    default: err = launch_gram_nb<6>(r, P1, Q1, w1, P2, Q2, w2, part, s); break;
   }
+  if (err != hipSuccess) return err;
   return launch_t_reduce(r, kTBlocks, part, out, s, accumulate);
 }
 
