@@ -244,7 +244,9 @@ k_mode(ModeArgs m, O out, int npanels) {
   constexpr int KSMAX = KS;
   extern __shared__ double mode_smem[];
   const int r = m.r;
-  double *T = mode_smem;  // [4 KS][LDT] input panel; rows >= r stay zero
+  // two [4 KS][LDT] input panels (double buffer); rows >= r stay zero
+  double *const T0 = mode_smem;
+  double *const T1 = mode_smem + 4 * KS * S::LDT;
   const int tid = threadIdx.x;
   const int lane = tid & 63, wave = tid >> 6;
   const int lr = lane & 15, lk = lane >> 4;
@@ -266,7 +268,7 @@ k_mode(ModeArgs m, O out, int npanels) {
       afr[q][ks] = ok ? v : 0.0;
     }
   }
-  for (int e = r * S::LDT + tid; e < 4 * KS * S::LDT; e += 256) T[e] = 0.0;
+  for (int e = r * S::LDT + tid; e < 4 * KS * S::LDT; e += 256) T0[e] = T1[e] = 0.0;
 
   // flat walk (Bn == 1): element f of the panel is column f / r, row f % r
   const int dc = 256 / r, dy = 256 - (256 / r) * r;
@@ -304,7 +306,7 @@ k_mode(ModeArgs m, O out, int npanels) {
     if constexpr (HAS2) return c1 * v1[k] + c2 * v2[k];
     else return c1 * v1[k];
   };
-  auto deposit = [&](int p) {
+  auto deposit = [&](int p, double *T) {
     const int nc = min(COLS, ncols - p * COLS);
     if (Bn == 1) {
       const int tot = nc * r;
@@ -327,9 +329,13 @@ k_mode(ModeArgs m, O out, int npanels) {
     }
   };
 
+  // iteration k multiplies the panel in buffer k & 1 while the next panel's
+  // loads are in flight; those land in buffer (k + 1) & 1 (last read in k - 1)
+  // before the one barrier of the iteration.
   int p = blockIdx.x;
+  int cur = 0;
   fetch(p);
-  deposit(p);
+  deposit(p, T0);
   __syncthreads();
   const double alpha = m.alpha;
   const int adiv = (int)m.adiv;
@@ -337,6 +343,7 @@ k_mode(ModeArgs m, O out, int npanels) {
     const int pn = p + (int)gridDim.x;
     const bool more = pn < npanels;
     if (more) fetch(pn);
+    const double *T = cur ? T1 : T0;
     mode_d4 acc[NRB][S::CB];
 #pragma unroll
     for (int q = 0; q < NRB; ++q)
@@ -374,9 +381,9 @@ k_mode(ModeArgs m, O out, int npanels) {
       }
     }
     if (!more) break;
-    __syncthreads();  // every wave is done reading the panel
-    deposit(pn);
+    deposit(pn, cur ? T0 : T1);
     __syncthreads();
+    cur ^= 1;
     p = pn;
   }
 }
@@ -931,13 +938,13 @@ hipError_t launch_f(int r, const double *Aaa, const double *Aab, const double *g
 
 // r <= 64: one 16-row block of M per wave, 32-column panels; r <= 96: two
 // row blocks per wave, 16-column panels (the prefetch stays at 8 per thread).
-// K steps rounded up to a multiple of 4 (at most 3 steps of zero padding).
+// K steps: exact for r <= 64; rounded up to a multiple of 4 above.
 static int mode_cols(int r) { return r <= 64 ? 32 : 16; }
-static int mode_ks(int r) { return (((r + 3) / 4) + 3) / 4 * 4; }
+static int mode_ks(int r) { return r <= 64 ? (r + 3) / 4 : ((((r + 3) / 4) + 3) / 4 * 4); }
 
 size_t mode_lds_bytes(int r) {
   const int ldt = mode_cols(r) + 1;
-  return (size_t)(4 * mode_ks(r) * ldt) * sizeof(double);
+  return (size_t)(2 * 4 * mode_ks(r) * ldt) * sizeof(double);
 }
 
 template <class O, int COLS, int NRB, bool HAS2, int KS>
@@ -965,10 +972,12 @@ static hipError_t launch_mode_t(const ModeArgs &m, O out, hipStream_t s) {
 template <class O, bool HAS2>
 static hipError_t launch_mode_h(const ModeArgs &m, O out, hipStream_t s) {
   switch (mode_ks(m.r)) {
-    case 4: return launch_mode_t<O, 32, 1, HAS2, 4>(m, out, s);
-    case 8: return launch_mode_t<O, 32, 1, HAS2, 8>(m, out, s);
-    case 12: return launch_mode_t<O, 32, 1, HAS2, 12>(m, out, s);
-    case 16: return launch_mode_t<O, 32, 1, HAS2, 16>(m, out, s);
+#define ACSE_MODE_KS(K) \
+    case K: return launch_mode_t<O, 32, 1, HAS2, K>(m, out, s);
+    ACSE_MODE_KS(1) ACSE_MODE_KS(2) ACSE_MODE_KS(3) ACSE_MODE_KS(4) ACSE_MODE_KS(5) ACSE_MODE_KS(6)
+    ACSE_MODE_KS(7) ACSE_MODE_KS(8) ACSE_MODE_KS(9) ACSE_MODE_KS(10) ACSE_MODE_KS(11)
+    ACSE_MODE_KS(12) ACSE_MODE_KS(13) ACSE_MODE_KS(14) ACSE_MODE_KS(15) ACSE_MODE_KS(16)
+#undef ACSE_MODE_KS
     case 20: return launch_mode_t<O, 16, 2, HAS2, 20>(m, out, s);
     default: return launch_mode_t<O, 16, 2, HAS2, 24>(m, out, s);
   }
