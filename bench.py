@@ -58,17 +58,17 @@ def parse():
     return ap.parse_args()
 
 
-# GEMM tile shapes (BM, BN, BK) per configuration index, as instantiated in gemm.hip
-TILE_SHAPES = {"fp64": [(128, 128, 16), (64, 64, 16), (128, 64, 16)],
-               "fp32": [(128, 128, 32), (64, 64, 32), (128, 64, 32)],
-               "bf16x3": [(128, 128, 32), (64, 64, 32), (128, 64, 32)]}
+# GEMM tile shapes (BM, BN, BK, LDS stages) per configuration index, as instantiated in gemm.hip
+TILE_SHAPES = {"fp64": [(128, 128, 16, 2), (64, 64, 16, 2), (128, 64, 16, 2)],
+               "fp32": [(128, 128, 32, 2), (64, 64, 32, 2), (128, 128, 64, 1)],
+               "bf16x3": [(128, 128, 32, 2), (64, 64, 32, 2), (128, 128, 64, 1)]}
 TRAITS = {"fp64": "TrF64", "fp32": "TrF32", "bf16x3": "TrBF16x3"}
 
 
 def gemm_kernel_name(prec, cfg):
-    bm, bn, bk = TILE_SHAPES[prec][cfg]
+    bm, bn, bk, ns = TILE_SHAPES[prec][cfg]
     wpe = 2 if prec == "fp64" and bm * bn >= 128 * 128 else 1   # register cap of the instantiation
-    return f"acse::gemm_nt_kernel<acse::{TRAITS[prec]}, {bm}, {bn}, {bk}, {wpe}>"
+    return f"acse::gemm_nt_kernel<acse::{TRAITS[prec]}, {bm}, {bn}, {bk}, {ns}, {wpe}>"
 
 
 def bench_batched(acse, ctx, gen, torch, modes, steps, warmup):

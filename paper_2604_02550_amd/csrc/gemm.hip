@@ -51,8 +51,11 @@ constexpr int kNumXcd = kGemmXcds;
 constexpr int kGroupM = 8;
 
 // One BM x BN output tile (and K chunk) of problem P; `local` counts the
-// problem's tiles in grouped order (split-major).
-template <class Tr, int BM, int BN, int BK>
+// problem's tiles in grouped order (split-major).  NS = 2: double-buffered LDS
+// slabs (one barrier per slab); NS = 1: one LDS slab (half the LDS, so twice
+// the resident workgroups for wide slabs), refilled from the register prefetch
+// between two barriers.
+template <class Tr, int BM, int BN, int BK, int NS>
 __device__ __forceinline__ void gemm_tile(const GemmProb &P, int local) {
   using T = typename Tr::T;
   using Acc = typename Tr::Acc;
@@ -68,8 +71,8 @@ __device__ __forceinline__ void gemm_tile(const GemmProb &P, int local) {
   static_assert(CH_B * VEC * NT == BN * BK, "B tile must split evenly");
   static_assert(BK % Tr::KSTEP == 0, "K tile must hold whole MFMA steps");
 
-  __shared__ __attribute__((aligned(16))) T As[2][NP][BM * LDK];
-  __shared__ __attribute__((aligned(16))) T Bs[2][NP][BN * LDK];
+  __shared__ __attribute__((aligned(16))) T As[NS][NP][BM * LDK];
+  __shared__ __attribute__((aligned(16))) T Bs[NS][NP][BN * LDK];
 
   // --- which tile / K chunk --------------------------------------------------
   const int per_split = P.tiles_m * P.tiles_n;
@@ -162,7 +165,7 @@ __device__ __forceinline__ void gemm_tile(const GemmProb &P, int local) {
     __syncthreads();
   }
   for (int kt = 0; kt < nk; ++kt) {
-    const int buf = kt & 1;
+    const int buf = NS == 2 ? (kt & 1) : 0;
     if (kt + 1 < nk) gload(kbeg + (kt + 1) * BK);
 #pragma unroll
     for (int kk = 0; kk < BK; kk += Tr::KSTEP) {
@@ -205,7 +208,10 @@ __device__ __forceinline__ void gemm_tile(const GemmProb &P, int local) {
           }
       }
     }
-    if (kt + 1 < nk) lstore(buf ^ 1);
+    if (kt + 1 < nk) {
+      if constexpr (NS == 1) __syncthreads();  // every wave is done with the slab
+      lstore(NS == 2 ? buf ^ 1 : 0);
+    }
     __syncthreads();
   }
 
@@ -250,7 +256,7 @@ template <class Tr, int BM, int BN>
 constexpr int gemm_wpe() { return (sizeof(typename Tr::T) == 8 && BM * BN >= 128 * 128) ? 2 : 1; }
 
 // One workgroup per tile; the (at most kMaxGemmProbs) problems travel by value.
-template <class Tr, int BM, int BN, int BK, int WPE>
+template <class Tr, int BM, int BN, int BK, int NS, int WPE>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WPE)))
 gemm_nt_kernel(const GemmBatch batch) {
   const int bid = xcd_logical(blockIdx.x, batch.total_tiles);
@@ -259,13 +265,13 @@ gemm_nt_kernel(const GemmBatch batch) {
     const int mid = (lo + hi + 1) >> 1;
     if (batch.seg_start[mid] <= bid) lo = mid; else hi = mid - 1;
   }
-  gemm_tile<Tr, BM, BN, BK>(batch.p[batch.seg_prob[lo]], batch.seg_local[lo] + bid - batch.seg_start[lo]);
+  gemm_tile<Tr, BM, BN, BK, NS>(batch.p[batch.seg_prob[lo]], batch.seg_local[lo] + bid - batch.seg_start[lo]);
 }
 
 // Persistent form for many problems: a grid sized to the resident capacity
 // walks the global tile list (problems ordered by decreasing K, so the long
 // tiles go first); workgroup w takes logical tiles w, w + G, w + 2G, ...
-template <class Tr, int BM, int BN, int BK, int WPE>
+template <class Tr, int BM, int BN, int BK, int NS, int WPE>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WPE)))
 gemm_nt_persistent(const GemmProb *__restrict__ probs, int count, int total) {
   const int G = gridDim.x;
@@ -276,7 +282,7 @@ gemm_nt_persistent(const GemmProb *__restrict__ probs, int count, int total) {
       if (probs[mid].tile_begin <= t) lo = mid; else hi = mid - 1;
     }
     const GemmProb P = probs[lo];
-    gemm_tile<Tr, BM, BN, BK>(P, t - P.tile_begin);
+    gemm_tile<Tr, BM, BN, BK, NS>(P, t - P.tile_begin);
     __syncthreads();  // the next tile restages LDS
   }
 }
@@ -285,19 +291,19 @@ gemm_nt_persistent(const GemmProb *__restrict__ probs, int count, int total) {
 // Configurations
 // ---------------------------------------------------------------------------
 namespace {
-struct Cfg { int bm, bn, bk; };
-constexpr Cfg kCfgF64[] = {{128, 128, 16}, {64, 64, 16}, {128, 64, 16}};
-constexpr Cfg kCfgF32[] = {{128, 128, 32}, {64, 64, 32}, {128, 64, 32}};
-constexpr Cfg kCfgBF[] = {{128, 128, 32}, {64, 64, 32}, {128, 64, 32}};
+struct Cfg { int bm, bn, bk, ns; };
+constexpr Cfg kCfgF64[] = {{128, 128, 16, 2}, {64, 64, 16, 2}, {128, 64, 16, 2}};
+constexpr Cfg kCfgF32[] = {{128, 128, 32, 2}, {64, 64, 32, 2}, {128, 128, 64, 1}};
+constexpr Cfg kCfgBF[] = {{128, 128, 32, 2}, {64, 64, 32, 2}, {128, 128, 64, 1}};
 
-template <class Tr, int BM, int BN, int BK>
+template <class Tr, int BM, int BN, int BK, int NS>
 hipError_t launch_one(const GemmBatch &b, hipStream_t s) {
-  hipLaunchKernelGGL((gemm_nt_kernel<Tr, BM, BN, BK, gemm_wpe<Tr, BM, BN>()>), dim3(b.total_tiles),
+  hipLaunchKernelGGL((gemm_nt_kernel<Tr, BM, BN, BK, NS, gemm_wpe<Tr, BM, BN>()>), dim3(b.total_tiles),
                      dim3(256), 0, s, b);
   return hipGetLastError();
 }
 
-template <class Tr, int BM, int BN, int BK>
+template <class Tr, int BM, int BN, int BK, int NS>
 hipError_t launch_persistent(const GemmProb *dprobs, int count, int total, hipStream_t s) {
   static int grid = 0;  // resident workgroups on the whole device (per instantiation)
   if (grid == 0) {
@@ -307,13 +313,13 @@ hipError_t launch_persistent(const GemmProb *dprobs, int count, int total, hipSt
     if (e == hipSuccess)
       e = hipOccupancyMaxActiveBlocksPerMultiprocessor(
           &per_cu,
-          reinterpret_cast<const void *>(&gemm_nt_persistent<Tr, BM, BN, BK, gemm_wpe<Tr, BM, BN>()>),
+          reinterpret_cast<const void *>(&gemm_nt_persistent<Tr, BM, BN, BK, NS, gemm_wpe<Tr, BM, BN>()>),
           256, 0);
     if (e != hipSuccess) return e;
     grid = std::max(kNumXcd, (cus * std::max(per_cu, 1)) / kNumXcd * kNumXcd);
   }
   const int g = std::min(grid, (int)round_up(total, kNumXcd));
-  hipLaunchKernelGGL((gemm_nt_persistent<Tr, BM, BN, BK, gemm_wpe<Tr, BM, BN>()>), dim3(g), dim3(256),
+  hipLaunchKernelGGL((gemm_nt_persistent<Tr, BM, BN, BK, NS, gemm_wpe<Tr, BM, BN>()>), dim3(g), dim3(256),
                      0, s, dprobs, count, total);
   return hipGetLastError();
 }
@@ -363,9 +369,9 @@ hipError_t gemm_launch(GemmPrec prec, int cfg, GemmBatch &b, hipStream_t s) {
   b.seg_start[b.nseg] = start;
 #define ACSE_GEMM_CASE(TR, CFGS)                                                          \
   switch (cfg) {                                                                          \
-    case 0: return launch_one<TR, CFGS[0].bm, CFGS[0].bn, CFGS[0].bk>(b, s);               \
-    case 1: return launch_one<TR, CFGS[1].bm, CFGS[1].bn, CFGS[1].bk>(b, s);               \
-    default: return launch_one<TR, CFGS[2].bm, CFGS[2].bn, CFGS[2].bk>(b, s);              \
+    case 0: return launch_one<TR, CFGS[0].bm, CFGS[0].bn, CFGS[0].bk, CFGS[0].ns>(b, s);               \
+    case 1: return launch_one<TR, CFGS[1].bm, CFGS[1].bn, CFGS[1].bk, CFGS[1].ns>(b, s);               \
+    default: return launch_one<TR, CFGS[2].bm, CFGS[2].bn, CFGS[2].bk, CFGS[2].ns>(b, s);              \
   }
   if (prec == GEMM_F64) { ACSE_GEMM_CASE(TrF64, kCfgF64) }
   if (prec == GEMM_F32) { ACSE_GEMM_CASE(TrF32, kCfgF32) }
@@ -395,9 +401,9 @@ hipError_t gemm_launch_persistent(GemmPrec prec, int cfg, std::vector<GemmProb> 
   if (e != hipSuccess) return e;
 #define ACSE_GEMM_CASE(TR, CFGS)                                                              \
   switch (cfg) {                                                                              \
-    case 0: return launch_persistent<TR, CFGS[0].bm, CFGS[0].bn, CFGS[0].bk>(dprobs, count, total, s); \
-    case 1: return launch_persistent<TR, CFGS[1].bm, CFGS[1].bn, CFGS[1].bk>(dprobs, count, total, s); \
-    default: return launch_persistent<TR, CFGS[2].bm, CFGS[2].bn, CFGS[2].bk>(dprobs, count, total, s); \
+    case 0: return launch_persistent<TR, CFGS[0].bm, CFGS[0].bn, CFGS[0].bk, CFGS[0].ns>(dprobs, count, total, s); \
+    case 1: return launch_persistent<TR, CFGS[1].bm, CFGS[1].bn, CFGS[1].bk, CFGS[1].ns>(dprobs, count, total, s); \
+    default: return launch_persistent<TR, CFGS[2].bm, CFGS[2].bn, CFGS[2].bk, CFGS[2].ns>(dprobs, count, total, s); \
   }
   if (prec == GEMM_F64) { ACSE_GEMM_CASE(TrF64, kCfgF64) }
   if (prec == GEMM_F32) { ACSE_GEMM_CASE(TrF32, kCfgF32) }
