@@ -179,11 +179,12 @@ typedef struct {
 acse_status acse_profile_enable(acse_ctx ctx, int32_t enable);
 acse_status acse_profile_read(acse_ctx ctx, acse_profile_data *out);
 
-/* Autotuner: times one residual map per GEMM tile configuration on this
- * problem (after a warm-up) and caches the fastest for (r, precision); later
- * calls with opts->tile = -1 use it.  Writes the chosen configuration index to
- * *best_tile and, if times_ms is not NULL, the grouped-GEMM time of every
- * configuration (times_ms[0..n-1], n = ACSE_NUM_TILE_CONFIGS).  Synchronises. */
+/* Autotuner: times the grouped GEMM of one residual map per tile
+ * configuration on this problem (one warm-up, then the fastest of three runs)
+ * and caches the fastest configuration for (r, precision); later calls with
+ * opts->tile = -1 use it.  Writes the chosen configuration index to
+ * *best_tile and, if times_ms is not NULL, the time of every configuration
+ * (times_ms[0..n-1], n = ACSE_NUM_TILE_CONFIGS).  Synchronises. */
 #define ACSE_NUM_TILE_CONFIGS 3
 acse_status acse_autotune(acse_ctx ctx, const acse_problem *prob, const acse_options *opts,
                           int32_t *best_tile, double *times_ms);

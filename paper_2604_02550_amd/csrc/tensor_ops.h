@@ -67,6 +67,11 @@ hipError_t launch_zero_kpad(GemmPrec prec, int r, int ld, const OperandRef &o, h
 hipError_t launch_f(int r, const double *Aaa, const double *Aab, const double *g, double *part,
                     double *f, hipStream_t s);
 hipError_t launch_mode(GemmPrec prec, const ModeArgs &m, const OperandRef &out, hipStream_t s);
+// out[k,l,:,:] = alpha g X[k,l,:,:] g for both blocks (g symmetric, r <= 64;
+// hipErrorInvalidValue above).
+constexpr int kSandwichMaxR = 64;
+hipError_t launch_sandwich(int r, const double *Xaa, const double *Xab, const double *g, double alpha,
+                           double *Oaa, double *Oab, hipStream_t s);
 // G2 (natural FP64) and the packed pp B operands B_aa, B_S, B_A.
 hipError_t launch_g2(GemmPrec prec, int r, const double *Aaa, const double *Aab, const double *Haa,
                      const double *Hab, const double *f, double *G2aa, double *G2ab,

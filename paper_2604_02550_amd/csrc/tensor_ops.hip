@@ -389,6 +389,116 @@ k_mode(ModeArgs m, O out, int npanels) {
 }
 
 // ---------------------------------------------------------------------------
+// Two-sided transform of r x r slices:  out[k,l,:,:] = alpha g X[k,l,:,:] g
+// (g symmetric) for the 2 r^2 slices of Xaa and Xab, i.e. C^T_kl = 4/3 g G2_kl g.
+// One pass over the data instead of two one-index transforms: per slice,
+// U = X_kl g and then g U on the FP64 MFMA, with the slice / U and g in LDS
+// (rows and columns >= r zero).  Wave w owns the 16-row output block w (NB
+// blocks per side, KS K steps of 4, both compile-time); persistent blocks walk
+// the slices with the next one prefetched into registers.
+// ---------------------------------------------------------------------------
+template <int NB, int KS>
+__global__ void __launch_bounds__(256)
+k_sandwich(int r, const double *__restrict__ Xaa, const double *__restrict__ Xab,
+           const double *__restrict__ g, double alpha, double *__restrict__ Oaa,
+           double *__restrict__ Oab) {
+  constexpr int N16 = NB * 16;
+  constexpr int LDX = N16 + 1;           // odd row stride
+  constexpr int PF = (N16 * N16) / 256;  // prefetched elements per thread (r^2 <= N16^2)
+  extern __shared__ double sw_smem[];
+  double *Xs = sw_smem;                  // [N16][LDX] slice, then U
+  double *Gs = sw_smem + N16 * LDX;      // [N16][LDX] g
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int lr = lane & 15, lk = lane >> 4;
+  const int r2 = r * r;
+  const int nsl = 2 * r2;
+  for (int e = tid; e < N16 * LDX; e += 256) {
+    const int a = e / LDX, b = e - (e / LDX) * LDX;
+    Gs[e] = (a < r && b < r) ? g[a * r + b] : 0.0;
+    Xs[e] = 0.0;
+  }
+  double v[PF];
+  auto fetch = [&](int sl) {
+    const double *src = (sl < r2 ? Xaa : Xab) + (int64_t)(sl < r2 ? sl : sl - r2) * r2;
+#pragma unroll
+    for (int q = 0; q < PF; ++q) v[q] = ld_ok(src, q * 256 + tid, q * 256 + tid < r2);
+  };
+  auto deposit = [&]() {
+#pragma unroll
+    for (int q = 0; q < PF; ++q) {
+      const int e = q * 256 + tid;
+      if (e < r2) {
+        const int a = e / r, b = e - (e / r) * r;
+        Xs[a * LDX + b] = v[q];
+      }
+    }
+  };
+  typedef double d4 __attribute__((ext_vector_type(4)));
+  int sl = blockIdx.x;
+  if (sl >= nsl) return;
+  fetch(sl);
+  __syncthreads();  // the zero fill is complete before the first deposit
+  deposit();
+  __syncthreads();
+  for (;;) {
+    const int nx = sl + (int)gridDim.x;
+    const bool more = nx < nsl;
+    if (more) fetch(nx);
+    d4 acc[NB];
+    // U[r', j] = sum_s X[r', s] g[j, s]
+#pragma unroll
+    for (int cb = 0; cb < NB; ++cb) acc[cb] = d4{0.0, 0.0, 0.0, 0.0};
+    if (wave < NB) {
+#pragma unroll
+      for (int ks = 0; ks < KS; ++ks) {
+        const int col = ks * 4 + lk;
+        const double a = Xs[(wave * 16 + lr) * LDX + col];
+#pragma unroll
+        for (int cb = 0; cb < NB; ++cb)
+          acc[cb] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, Gs[(cb * 16 + lr) * LDX + col], acc[cb], 0, 0, 0);
+      }
+    }
+    __syncthreads();  // every wave is done reading the slice
+    if (wave < NB) {
+      // accumulator item q of lane l: row lk + 4q, column lr of the block
+#pragma unroll
+      for (int cb = 0; cb < NB; ++cb)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) Xs[(wave * 16 + lk + 4 * q) * LDX + cb * 16 + lr] = acc[cb][q];
+    }
+    __syncthreads();
+    // out[i, j] = alpha sum_r' g[i, r'] U[r', j]
+#pragma unroll
+    for (int cb = 0; cb < NB; ++cb) acc[cb] = d4{0.0, 0.0, 0.0, 0.0};
+    if (wave < NB) {
+#pragma unroll
+      for (int ks = 0; ks < KS; ++ks) {
+        const int kr = ks * 4 + lk;
+        const double a = Gs[(wave * 16 + lr) * LDX + kr];
+#pragma unroll
+        for (int cb = 0; cb < NB; ++cb)
+          acc[cb] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, Xs[kr * LDX + cb * 16 + lr], acc[cb], 0, 0, 0);
+      }
+      double *dst = (sl < r2 ? Oaa : Oab) + (int64_t)(sl < r2 ? sl : sl - r2) * r2;
+#pragma unroll
+      for (int cb = 0; cb < NB; ++cb) {
+        const int j = cb * 16 + lr;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const int i = wave * 16 + lk + 4 * q;
+          if (i < r && j < r) dst[i * r + j] = alpha * acc[cb][q];
+        }
+      }
+    }
+    if (!more) break;
+    __syncthreads();  // every wave is done reading U
+    deposit();
+    __syncthreads();
+    sl = nx;
+  }
+}
+
+// ---------------------------------------------------------------------------
 // G2 tensors (fold of the f and H terms) and the packed pp B operands:
 //   G2_aa[k,l,r,s] = H_aa[k,l,r,s] - H_aa[l,k,r,s]
 //                    + f[k,r] d_ls - f[k,s] d_lr - f[l,r] d_ks + f[l,s] d_kr
@@ -986,6 +1096,39 @@ static hipError_t launch_mode_h(const ModeArgs &m, O out, hipStream_t s) {
 template <class O>
 static hipError_t launch_mode_o(const ModeArgs &m, O out, hipStream_t s) {
   return m.in2 ? launch_mode_h<O, true>(m, out, s) : launch_mode_h<O, false>(m, out, s);
+}
+
+template <int NB, int KS>
+static hipError_t launch_sandwich_t(int r, const double *Xaa, const double *Xab, const double *g,
+                                    double alpha, double *Oaa, double *Oab, hipStream_t s) {
+  static int resident = 0;  // blocks the device holds at once
+  const size_t lds = (size_t)2 * (NB * 16) * (NB * 16 + 1) * sizeof(double);
+  const void *fn = reinterpret_cast<const void *>(&k_sandwich<NB, KS>);
+  if (resident == 0) {
+    int dev = 0, cus = 0, per_cu = 0;
+    hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e == hipSuccess) e = hipGetDevice(&dev);
+    if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    if (e == hipSuccess) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, 256, lds);
+    if (e != hipSuccess) return e;
+    resident = cus * std::max(per_cu, 1);
+  }
+  const int nsl = 2 * r * r;
+  hipLaunchKernelGGL((k_sandwich<NB, KS>), dim3(std::min(nsl, resident)), dim3(256), lds, s, r, Xaa, Xab,
+                     g, alpha, Oaa, Oab);
+  return hipGetLastError();
+}
+
+hipError_t launch_sandwich(int r, const double *Xaa, const double *Xab, const double *g, double alpha,
+                           double *Oaa, double *Oab, hipStream_t s) {
+  switch ((r + 3) / 4) {
+#define ACSE_SW(K) \
+    case K: return launch_sandwich_t<(4 * K + 15) / 16, K>(r, Xaa, Xab, g, alpha, Oaa, Oab, s);
+    ACSE_SW(1) ACSE_SW(2) ACSE_SW(3) ACSE_SW(4) ACSE_SW(5) ACSE_SW(6) ACSE_SW(7) ACSE_SW(8)
+    ACSE_SW(9) ACSE_SW(10) ACSE_SW(11) ACSE_SW(12) ACSE_SW(13) ACSE_SW(14) ACSE_SW(15) ACSE_SW(16)
+#undef ACSE_SW
+    default: return hipErrorInvalidValue;  // r > 64: the caller uses two one-index transforms
+  }
 }
 
 hipError_t launch_mode(GemmPrec prec, const ModeArgs &m, const OperandRef &out, hipStream_t s) {
