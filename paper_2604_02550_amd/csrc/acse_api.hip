@@ -631,13 +631,9 @@ acse_status acse_step(acse_ctx ctx, acse_problem *prob, double eps, const acse_o
   // 2D <- 2D + eps U, trace restoration, 1-RDM contraction, energy (FP64)
   {
     StageTimer t5(ctx, 5);
-    HIP_TRY(ctx, launch_traces(r, prob->d2aa, prob->d2ab, w.scal + 4, s));
-    HIP_TRY(ctx, launch_axpy2(r, eps, prob->d2aa, prob->d2ab, Uaa, Uab, w.Naa, w.Nab, s));
-    HIP_TRY(ctx, launch_traces(r, w.Naa, w.Nab, w.scal + 6, s));
-    HIP_TRY(ctx, launch_rescale(r, w.scal + 4, w.Naa, w.Nab, prob->d2aa, prob->d2ab, s));
+    HIP_TRY(ctx, launch_step_tail(r, N, eps, prob->h, prob->V, Uaa, Uab, prob->d2aa, prob->d2ab,
+                                  w.scal + 4, w.partial, w.scal + 1, s));
     HIP_TRY(ctx, launch_contract_1rdm(r, N, prob->d2aa, prob->d2ab, prob->d1, s));
-    HIP_TRY(ctx, launch_energy(r, N, prob->h, prob->V, prob->d2aa, prob->d2ab, w.partial,
-                               w.scal + 1, s));
   }
   return fetch_scalars(ctx, norm2_host, E_host);
 }

@@ -99,6 +99,11 @@ hipError_t launch_t(int r, const double *Waa, const double *Aaa, const double *W
                     const double *Aab, double *part, double *t, hipStream_t s);
 hipError_t launch_energy(int r, int N, const double *h, const double *V, const double *d2aa,
                          const double *d2ab, double *partial, double *E_out, hipStream_t s);
+// 2D <- (2D + eps U) rescaled to the input trace per block (in place), the
+// traces [in_aa, in_ab, new_aa, new_ab] and the energy Tr(K 2D) of the result.
+hipError_t launch_step_tail(int r, int N, double eps, const double *h, const double *V,
+                            const double *Uaa, const double *Uab, double *d2aa, double *d2ab,
+                            double *traces, double *partial, double *E_out, hipStream_t s);
 hipError_t launch_traces(int r, const double *d2aa, const double *d2ab, double *traces,
                          hipStream_t s);
 hipError_t launch_axpy2(int r, double eps, const double *aa, const double *ab, const double *Uaa,

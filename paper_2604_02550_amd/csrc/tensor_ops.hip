@@ -199,13 +199,18 @@ __global__ void k_f_partial(int r, const double *__restrict__ Aaa, const double 
     acc += (Aaa[base + (int64_t)rr * r + s] - Aab[base + (int64_t)s * r + rr]) * g[p * r + rr];
   part[e] = acc;  // [k][p][s]
 }
-__global__ void k_f_reduce(int r, const double *__restrict__ part, double *__restrict__ f) {
-  const int e = (int)gtid();
+// f[k,s] = sum_p part[k,p,s]: one wavefront per output, lanes over p,
+// fixed-order shuffle reduction.
+__global__ void __launch_bounds__(256)
+k_f_reduce(int r, const double *__restrict__ part, double *__restrict__ f) {
+  const int lane = threadIdx.x & 63;
+  const int e = blockIdx.x * 4 + (threadIdx.x >> 6);
   if (e >= r * r) return;
   const int k = e / r, s = e % r;
   double acc = 0.0;
-  for (int p = 0; p < r; ++p) acc += part[((int64_t)k * r + p) * r + s];
-  f[e] = acc;
+  for (int p = lane; p < r; p += 64) acc += part[((int64_t)k * r + p) * r + s];
+  for (int off = 32; off > 0; off >>= 1) acc += __shfl_down(acc, off, 64);
+  if (lane == 0) f[e] = acc;
 }
 
 // ---------------------------------------------------------------------------
@@ -953,19 +958,86 @@ __global__ void k_rescale(int64_t n, const double *__restrict__ traces, const do
   d2ab[e] = nab[e] * sb;
 }
 
-// gamma[p,r] = 2/(N-1) sum_q (d2aa[p,q,r,q] + d2ab[p,q,r,q])
-__global__ void k_contract_1rdm(int r, double two_over_nm1, const double *__restrict__ d2aa,
-                                const double *__restrict__ d2ab, double *__restrict__ g) {
-  const int e = (int)gtid();
+// gamma[p,r] = 2/(N-1) sum_q (d2aa[p,q,r,q] + d2ab[p,q,r,q]): one wavefront per
+// output, lanes over q, fixed-order shuffle reduction.
+__global__ void __launch_bounds__(256)
+k_contract_1rdm(int r, double two_over_nm1, const double *__restrict__ d2aa,
+                const double *__restrict__ d2ab, double *__restrict__ g) {
+  const int lane = threadIdx.x & 63;
+  const int e = blockIdx.x * 4 + (threadIdx.x >> 6);
   if (e >= r * r) return;
   const int p = e / r, rr = e % r;
   const int64_t r2 = (int64_t)r * r;
   double acc = 0.0;
-  for (int q = 0; q < r; ++q) {
+  for (int q = lane; q < r; q += 64) {
     const int64_t o = ((int64_t)p * r + q) * r2 + (int64_t)rr * r + q;
     acc += d2aa[o] + d2ab[o];
   }
-  g[e] = two_over_nm1 * acc;
+  for (int off = 32; off > 0; off >>= 1) acc += __shfl_down(acc, off, 64);
+  if (lane == 0) g[e] = two_over_nm1 * acc;
+}
+
+// Fused step tail (one block computes the traces, one pass updates):
+//   traces[0..3] = (Tr d2aa, Tr d2ab, Tr(d2aa + eps U_aa), Tr(d2ab + eps U_ab)),
+//   d2 <- (d2 + eps U) * (Tr_in / Tr_new) per block, in place, and the energy
+//   partials 2 K_s (d2aa + d2ab) of the updated blocks.  The updated element is
+//   fma(eps, U, d2) in both kernels, so the trace matches the update exactly.
+__global__ void __launch_bounds__(256)
+k_step_traces(int r, double eps, const double *__restrict__ d2aa, const double *__restrict__ d2ab,
+              const double *__restrict__ Uaa, const double *__restrict__ Uab,
+              double *__restrict__ traces) {
+  __shared__ double red[4][256];
+  const int64_t r2 = (int64_t)r * r;
+  double a = 0.0, b = 0.0, na = 0.0, nb = 0.0;
+  for (int64_t q = threadIdx.x; q < r2; q += 256) {
+    const int64_t d = q * r2 + q;  // element (p,q,p,q) at row = col = p*r+q
+    a += d2aa[d];
+    b += d2ab[d];
+    na += fma(eps, Uaa[d], d2aa[d]);
+    nb += fma(eps, Uab[d], d2ab[d]);
+  }
+  red[0][threadIdx.x] = a;
+  red[1][threadIdx.x] = b;
+  red[2][threadIdx.x] = na;
+  red[3][threadIdx.x] = nb;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if (threadIdx.x < w)
+      for (int k = 0; k < 4; ++k) red[k][threadIdx.x] += red[k][threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x < 4) traces[threadIdx.x] = red[threadIdx.x][0];
+}
+
+__global__ void __launch_bounds__(256)
+k_step_update(int r, double eps, double inv_nm1, const double *__restrict__ traces,
+              const double *__restrict__ h, const double *__restrict__ V,
+              const double *__restrict__ Uaa, const double *__restrict__ Uab,
+              double *__restrict__ d2aa, double *__restrict__ d2ab, double *__restrict__ partial) {
+  __shared__ double red[256];
+  const int64_t r2 = (int64_t)r * r;
+  const int64_t n4 = r2 * r2;
+  const int64_t e = gtid();
+  double acc = 0.0;
+  if (e < n4) {
+    const double sa = traces[0] / traces[2], sb = traces[1] / traces[3];
+    const double naa = fma(eps, Uaa[e], d2aa[e]) * sa;
+    const double nab = fma(eps, Uab[e], d2ab[e]) * sb;
+    d2aa[e] = naa;
+    d2ab[e] = nab;
+    const int s = e % r, rr = (e / r) % r, q = (e / r2) % r, p = e / (r2 * r);
+    double ks = V[(int64_t)p * r2 * r + (int64_t)rr * r2 + (int64_t)q * r + s];
+    if (q == s) ks += h[p * r + rr] * inv_nm1;
+    if (p == rr) ks += h[q * r + s] * inv_nm1;
+    acc = 2.0 * ks * (naa + nab);
+  }
+  red[threadIdx.x] = acc;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) partial[blockIdx.x] = red[0];
 }
 
 __global__ void k_fill(int64_t n, double v, double *__restrict__ p) {
@@ -1042,7 +1114,7 @@ hipError_t launch_f(int r, const double *Aaa, const double *Aab, const double *g
                     double *f, hipStream_t s) {
   const int64_t r3 = (int64_t)r * r * r;
   hipLaunchKernelGGL(k_f_partial, grid_for(r3), dim3(256), 0, s, r, Aaa, Aab, g, part);
-  hipLaunchKernelGGL(k_f_reduce, grid_for((int64_t)r * r), dim3(256), 0, s, r, part, f);
+  hipLaunchKernelGGL(k_f_reduce, dim3((unsigned)((r * r + 3) / 4)), dim3(256), 0, s, r, part, f);
   return hipGetLastError();
 }
 
@@ -1241,6 +1313,18 @@ hipError_t launch_energy(int r, int N, const double *h, const double *V, const d
   return hipGetLastError();
 }
 
+hipError_t launch_step_tail(int r, int N, double eps, const double *h, const double *V,
+                            const double *Uaa, const double *Uab, double *d2aa, double *d2ab,
+                            double *traces, double *partial, double *E_out, hipStream_t s) {
+  const int64_t n4 = (int64_t)r * r * r * r;
+  const int64_t nb = (n4 + 255) / 256;
+  hipLaunchKernelGGL(k_step_traces, dim3(1), dim3(256), 0, s, r, eps, d2aa, d2ab, Uaa, Uab, traces);
+  hipLaunchKernelGGL(k_step_update, dim3((unsigned)nb), dim3(256), 0, s, r, eps, 1.0 / (N - 1), traces,
+                     h, V, Uaa, Uab, d2aa, d2ab, partial);
+  hipLaunchKernelGGL(k_reduce_sum, dim3(1), dim3(256), 0, s, nb, partial, E_out);
+  return hipGetLastError();
+}
+
 hipError_t launch_traces(int r, const double *d2aa, const double *d2ab, double *traces, hipStream_t s) {
   hipLaunchKernelGGL(k_traces, dim3(1), dim3(256), 0, s, r, d2aa, d2ab, traces);
   return hipGetLastError();
@@ -1262,7 +1346,7 @@ hipError_t launch_rescale(int r, const double *traces, const double *naa, const 
 
 hipError_t launch_contract_1rdm(int r, int N, const double *d2aa, const double *d2ab, double *g,
                                 hipStream_t s) {
-  hipLaunchKernelGGL(k_contract_1rdm, grid_for((int64_t)r * r), dim3(256), 0, s, r, 2.0 / (N - 1),
+  hipLaunchKernelGGL(k_contract_1rdm, dim3((unsigned)((r * r + 3) / 4)), dim3(256), 0, s, r, 2.0 / (N - 1),
                      d2aa, d2ab, g);
   return hipGetLastError();
 }
