@@ -250,9 +250,8 @@ def main():
     traffic = None
     if os.path.exists(TRAFFIC):
         t = json.load(open(TRAFFIC))
-        k = t.get("kernels", {}).get(head)
-        if (t.get("gemm_src_sha256_16") == src_hash() and k is not None
-                and k.get("kernel") == gemm_kernel_name(head, hr["tile_config"])):
+        k = t.get("kernels", {}).get(gemm_kernel_name(head, hr["tile_config"]))
+        if t.get("gemm_src_sha256_16") == src_hash() and k is not None:
             traffic = k.get("bytes_per_launch")
     line = {
         "metric": "ACSE residual evals/s + TFLOP/s at r=50: FP64 vs mixed at |dE|<1e-7 Eh",
