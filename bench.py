@@ -51,6 +51,8 @@ def parse():
     ap.add_argument("--modes", default="fp64,fp32,bf16x3")
     ap.add_argument("--eps", type=float, default=1e-3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--vjp-modes", default="fp64,fp32",
+                    help="precisions of the adjoint (VJP) measurement ('' to skip)")
     ap.add_argument("--batched-modes", default="fp64,fp32",
                     help="precisions of the batched-instances measurement ('' to skip)")
     ap.add_argument("--calibrate-copy-mib", type=int, default=0,
@@ -128,6 +130,47 @@ def bench_batched(acse, ctx, gen, torch, modes, steps, warmup):
                          persistent_gemm_ms=gemm_ms,
                          persistent_gemm_tflops=flops / (gemm_ms * 1e-3) / 1e12,
                          useful_tflops=flops / (ms_b * 1e-3) / 1e12)
+    return res
+
+
+def bench_vjp(acse, gen, torch, modes, steps, warmup):
+    """acse_residual_vjp with a seeded cotangent: on the differentiation workload
+    (r = 30, N = 20) and on r = 50, N = 30, against the forward residual of the
+    same problem (one context per size)."""
+    dev = torch.device("cuda", 0)
+    res = {}
+    for wl in ("vjp30", "r50"):
+        p = gen.named(wl)
+        r = p["r"]
+        ctx = acse.Context(r_max=r, device=0)
+        prob, keep = ctx.problem(p["h"], p["V"], p["gamma"], p["d2aa"], p["d2ab"], p["N"] // 2)
+        Rb = [torch.as_tensor(a, device=dev).contiguous() for a in gen.cotangent(np.random.default_rng(5), r)]
+        outs = [torch.empty_like(t) for t in keep]
+        R = [torch.empty((r, r, r, r), dtype=torch.float64, device=dev) for _ in range(2)]
+        for mode in modes:
+            opts = acse.Context.options(mode)
+            ctx.autotune_raw(prob, opts)
+
+            def timed(fn):
+                for _ in range(warmup):
+                    fn()
+                torch.cuda.synchronize()
+                a = torch.cuda.Event(enable_timing=True)
+                b = torch.cuda.Event(enable_timing=True)
+                a.record(ctx.stream)
+                for _ in range(steps):
+                    fn()
+                b.record(ctx.stream)
+                torch.cuda.synchronize()
+                return a.elapsed_time(b) / steps
+
+            ms_vjp = timed(lambda: ctx.residual_vjp_raw(prob, opts, Rb[0], Rb[1], *outs))
+            ms_fwd = timed(lambda: ctx.residual_raw(prob, opts, R[0], R[1], want_norm=False))
+            res[f"{wl}_{mode}"] = dict(r=r, vjp_ms=ms_vjp, residual_ms=ms_fwd, vjp_over_residual=ms_vjp / ms_fwd,
+                                       vjp_per_s=1e3 / ms_vjp)
+        ctx.close()
+        del keep, outs, R, Rb
+        torch.cuda.empty_cache()
     return res
 
 
@@ -278,6 +321,9 @@ def main():
         "residual_only_evals_per_s": hr["residual_evals_per_s"],
         "modes": results,
     }
+    if args.vjp_modes:
+        line["vjp"] = bench_vjp(acse, gen, torch, args.vjp_modes.split(","), max(3, args.steps // 2),
+                                args.warmup)
     if args.batched_modes:
         line["batched_instances"] = bench_batched(acse, ctx, gen, torch, args.batched_modes.split(","),
                                                   args.steps, args.warmup)
