@@ -762,19 +762,8 @@ extern "C" acse_status acse_residual_vjp(acse_ctx ctx, const acse_problem *prob,
                       r2, 1, 1, 0));
   HIP_TRY(ctx, launch_g2(prec, r, w.Aaa, w.Aab, w.Haa, w.Hab, w.f, w.G2aa, w.G2ab, vop(0), vop(1), vop(2),
                          s));
-  double *Baa = V[0], *Bab = V[1], *Lp = V[2], *Lm = V[3], *L3 = V[4], *Rp = V[5], *Rm = V[6], *R3 = V[7];
-  HIP_TRY(ctx, permute(GEMM_F64, natref(Baa), false, w.Aaa, ID, 1.0, w.G2aa, ID, -1.0, 0));
-  HIP_TRY(ctx, permute(GEMM_F64, natref(Bab), false, w.Aab, ID, 1.0, w.G2ab, ID, -1.0, 0));
-  // L+-[k,i,p,s] = sum_r g[i,r] (A_aa +- A_ab)[k,p,r,s];  L3[k,j,p,s] = sum_r g[j,r] A_ab[k,p,s,r]
-  HIP_TRY(ctx, mode(w.Aaa, w.Aab, 1.0, g, 0, r2, r, 1.0, Lp, r, r3, r, r2, 1, 1, 0));
-  HIP_TRY(ctx, mode(w.Aaa, w.Aab, -1.0, g, 0, r2, r, 1.0, Lm, r, r3, r, r2, 1, 1, 0));
-  HIP_TRY(ctx, mode(w.Aab, nullptr, 0.0, g, 0, r3, 1, 1.0, L3, r2, r3, 1, r2, 0, 1, 0));
-  {  // R+-[j,l,p,s] = W_aa[j,p,s,l] -+ W_ab[j,p,l,s];  R3[i,l,p,s] = W_ab[i,p,s,l]
-    const int ma[4] = {0, 3, 1, 2}, mb[4] = {0, 2, 1, 3};
-    HIP_TRY(ctx, permute(GEMM_F64, natref(Rp), false, w.Waa, ma, 1.0, w.Wab, mb, -1.0, 0));
-    HIP_TRY(ctx, permute(GEMM_F64, natref(Rm), false, w.Waa, ma, 1.0, w.Wab, mb, 1.0, 0));
-    HIP_TRY(ctx, permute(GEMM_F64, natref(R3), false, w.Wab, ma, 1.0, nullptr, ID, 0.0, 0));
-  }
+  // B = A - G2, L+-, L3 and R+-, R3 are written straight into the GEMM operand
+  // layouts where the products below need them.
 
   // ---------------- backward ----------------------------------------------
   double *Sbaa = V[8], *Sbab = V[9], *Ppb = V[10], *Pmb = V[11], *E3b = V[12];
@@ -811,26 +800,42 @@ extern "C" acse_status acse_residual_vjp(acse_ctx ctx, const acse_problem *prob,
     P.sm1 = nat.S[om[0]]; P.sm0 = nat.S[om[1]]; P.sn1 = nat.S[om[2]]; P.sn0 = nat.S[om[3]];
     P.ksplit = 1; P.kchunk = ld; P.accumulate = 0;
   };
-  const int use_cfg = opts && opts->tile >= 0 ? opts->tile : gemm_default_cfg(prec, (int)r2, (int)r2);
+  int use_cfg = opts ? opts->tile : -1;
+  if (use_cfg < 0) {
+    auto it = ctx->tuned.find({r, (int)prec});
+    use_cfg = it != ctx->tuned.end() ? it->second : gemm_default_cfg(prec, (int)r2, (int)r2);
+  }
   {  // particle-hole adjoint products
     // L+b[(k,i),(p,s)] = sum_(j,l) P+b[i,j,k,l] R+[j,l,p,s];  R+b[(j,l),(p,s)] = sum_(k,i) P+b L+[k,i,p,s]
     const int Akijl[4] = {2, 0, 1, 3}, Ajlki[4] = {1, 3, 2, 0};
-    const int Bps_jl[4] = {2, 3, 0, 1};   // R[j,l,p,s] as rows (p,s), cols (j,l)
-    const int Bps_ki[4] = {2, 3, 0, 1};   // L[k,i,p,s] as rows (p,s), cols (k,i)
     const int Akjil[4] = {2, 1, 0, 3}, Ailkj[4] = {0, 3, 2, 1};
+    // R+-[j,l,p,s] = W_aa[j,p,s,l] -+ W_ab[j,p,l,s], R3[i,l,p,s] = W_ab[i,p,s,l], as rows (p,s), cols (j,l)
+    const int Rwaa[4] = {1, 2, 0, 3}, Rwab[4] = {1, 3, 0, 2};
+    // L+-[k,i,p,s] = sum_r g[i,r] (A_aa +- A_ab)[k,p,r,s], L3[k,j,p,s] = sum_r g[j,r] A_ab[k,p,s,r],
+    // as rows (p,s), cols (k,i): written by the mode products with operand strides
+    auto lop = [&](int q, const double *in1, const double *in2, double c2, int64_t A, int64_t Bn,
+                   int64_t adiv, int64_t so1, int64_t so0, int64_t sb) -> hipError_t {
+      hipError_t e = launch_zero_kpad(prec, r, ld, vop(q), s);
+      if (e != hipSuccess) return e;
+      ModeArgs m = mode_base(r, g);
+      m.A = A; m.Bn = Bn; m.in1 = in1; m.in2 = in2; m.c2 = c2;
+      m.adiv = adiv; m.so1 = so1; m.so0 = so0; m.sx = 1; m.sb = sb; m.out_cols_fast = 1;
+      return launch_mode(prec, m, vop(q), s);
+    };
     HIP_TRY(ctx, permute(prec, vop(0), true, Ppb, Akijl, 1.0, nullptr, ID, 0.0, 0));
-    HIP_TRY(ctx, permute(prec, vop(1), true, Rp, Bps_jl, 1.0, nullptr, ID, 0.0, 0));
+    HIP_TRY(ctx, permute(prec, vop(1), true, w.Waa, Rwaa, 1.0, w.Wab, Rwab, -1.0, 0));
     HIP_TRY(ctx, permute(prec, vop(2), true, Ppb, Ajlki, 1.0, nullptr, ID, 0.0, 0));
-    HIP_TRY(ctx, permute(prec, vop(3), true, Lp, Bps_ki, 1.0, nullptr, ID, 0.0, 0));
+    HIP_TRY(ctx, lop(3, w.Aaa, w.Aab, 1.0, r2, r, r, r, (int64_t)r * ld, ld));
     HIP_TRY(ctx, permute(prec, vop(4), true, Pmb, Akijl, 1.0, nullptr, ID, 0.0, 0));
-    HIP_TRY(ctx, permute(prec, vop(5), true, Rm, Bps_jl, 1.0, nullptr, ID, 0.0, 0));
+    HIP_TRY(ctx, permute(prec, vop(5), true, w.Waa, Rwaa, 1.0, w.Wab, Rwab, 1.0, 0));
     HIP_TRY(ctx, permute(prec, vop(6), true, Pmb, Ajlki, 1.0, nullptr, ID, 0.0, 0));
-    HIP_TRY(ctx, permute(prec, vop(7), true, Lm, Bps_ki, 1.0, nullptr, ID, 0.0, 0));
+    HIP_TRY(ctx, lop(7, w.Aaa, w.Aab, -1.0, r2, r, r, r, (int64_t)r * ld, ld));
     // L3b[(k,j),(p,s)] = -2 sum_(i,l) E3b[i,j,k,l] R3[i,l,p,s];  R3b[(i,l),(p,s)] = -2 sum_(k,j) E3b L3[k,j,p,s]
     HIP_TRY(ctx, permute(prec, vop(8), true, E3b, Akjil, 1.0, nullptr, ID, 0.0, 0));
-    HIP_TRY(ctx, permute(prec, vop(9), true, R3, Bps_jl, 1.0, nullptr, ID, 0.0, 0));
+    HIP_TRY(ctx, permute(prec, vop(9), true, w.Wab, Rwaa, 1.0, nullptr, ID, 0.0, 0));
     HIP_TRY(ctx, permute(prec, vop(10), true, E3b, Ailkj, 1.0, nullptr, ID, 0.0, 0));
-    HIP_TRY(ctx, permute(prec, vop(11), true, L3, Bps_ki, 1.0, nullptr, ID, 0.0, 0));
+    HIP_TRY(ctx, lop(11, w.Aab, nullptr, 0.0, r3, 1, r2, r, ld, 0));
+
     GemmBatch b{};
     b.count = 6;
     gemm_set(b, 0, 0, 1, 1.0, Lpb, ID);
@@ -850,13 +855,13 @@ extern "C" acse_status acse_residual_vjp(acse_ctx ctx, const acse_problem *prob,
     // aa block
     HIP_TRY(ctx, permute(prec, vop(0), true, Sbaa, ID, 1.0, nullptr, ID, 0.0, 0));
     HIP_TRY(ctx, permute(prec, vop(1), true, Sbaa, Akl_ij, 1.0, nullptr, ID, 0.0, 0));
-    HIP_TRY(ctx, permute(prec, vop(2), true, Baa, Brs_kl, 1.0, nullptr, ID, 0.0, 0));
+    HIP_TRY(ctx, permute(prec, vop(2), true, w.Aaa, Brs_kl, 1.0, w.G2aa, Brs_kl, -1.0, 0));  // B = A - G2
     HIP_TRY(ctx, permute(prec, vop(3), true, prob->d2aa, Brs_kl, 1.0, nullptr, ID, 0.0, 0));
     HIP_TRY(ctx, permute(prec, vop(4), true, w.G2aa, Brs_kl, 1.0, nullptr, ID, 0.0, 0));
     // ab block
     HIP_TRY(ctx, permute(prec, vop(5), true, Sbab, ID, 1.0, nullptr, ID, 0.0, 0));
     HIP_TRY(ctx, permute(prec, vop(6), true, Sbab, Akl_ij, 1.0, nullptr, ID, 0.0, 0));
-    HIP_TRY(ctx, permute(prec, vop(7), true, Bab, Brs_kl, 1.0, nullptr, ID, 0.0, 0));
+    HIP_TRY(ctx, permute(prec, vop(7), true, w.Aab, Brs_kl, 1.0, w.G2ab, Brs_kl, -1.0, 0));
     HIP_TRY(ctx, permute(prec, vop(8), true, prob->d2ab, Brs_kl, 1.0, nullptr, ID, 0.0, 0));
     HIP_TRY(ctx, permute(prec, vop(9), true, w.G2ab, Brs_kl, 1.0, nullptr, ID, 0.0, 0));
     GemmBatch b{};

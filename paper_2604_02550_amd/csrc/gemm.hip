@@ -333,10 +333,11 @@ GemmTileInfo gemm_tile_info(GemmPrec prec, int cfg) {
 }
 
 int gemm_default_cfg(GemmPrec prec, int M, int N) {
-  // Large tiles once there are enough of them to fill 256 CUs twice over.
+  // 128 x 128 tiles (the wide-K single-stage one for FP32 / split BF16) once a
+  // grouped launch of such products has a few per CU; 64 x 64 below.
   const int64_t big = ((M + 127) / 128) * (int64_t)((N + 127) / 128);
-  (void)prec;
-  return big >= 512 ? 0 : 1;
+  if (big < 128) return 1;
+  return prec == GEMM_F64 ? 0 : 2;
 }
 
 hipError_t gemm_launch(GemmPrec prec, int cfg, GemmBatch &b, hipStream_t s) {
