@@ -181,7 +181,8 @@ acse_status acse_profile_read(acse_ctx ctx, acse_profile_data *out);
 
 /* Autotuner: times the grouped GEMM of one residual map per tile
  * configuration on this problem (one warm-up, then the fastest of three runs)
- * and caches the fastest configuration for (r, precision); later calls with
+ * and caches the fastest configuration for (r, precision) (the size default
+ * is kept unless another configuration is at least 3% faster); later calls with
  * opts->tile = -1 use it.  Writes the chosen configuration index to
  * *best_tile and, if times_ms is not NULL, the time of every configuration
  * (times_ms[0..n-1], n = ACSE_NUM_TILE_CONFIGS).  Synchronises. */

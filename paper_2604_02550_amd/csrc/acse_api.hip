@@ -367,6 +367,15 @@ ActiveBits make_bits(const acse_options *o, int r, bool *any) {
   return b;
 }
 
+// The autotuners keep the size default unless another tile shape is at least
+// kTuneMargin faster: the single-map timings they take are noisier than the
+// differences between close configurations.
+constexpr double kTuneMargin = 0.03;
+int keep_default(int best_cfg, double best_ms, int default_cfg, const double *times_ms) {
+  if (!times_ms || best_cfg == default_cfg) return best_cfg;
+  return times_ms[default_cfg] <= best_ms * (1.0 + kTuneMargin) ? default_cfg : best_cfg;
+}
+
 acse_status fetch_scalars(acse_ctx c, double *norm2_host, double *E_host) {
   if (!norm2_host && !E_host) return ACSE_OK;
   double host[2] = {0.0, 0.0};
@@ -529,6 +538,7 @@ acse_status acse_autotune(acse_ctx ctx, const acse_problem *prob, const acse_opt
   ctx->recs.clear();
   double best = 1e300;
   int arg = 0;
+  double tms[ACSE_NUM_TILE_CONFIGS] = {};
   const ActiveBits none{};
   for (int cfg = 0; cfg < ACSE_NUM_TILE_CONFIGS; ++cfg) {
     ctx->profiling = false;
@@ -553,12 +563,14 @@ acse_status acse_autotune(acse_ctx ctx, const acse_problem *prob, const acse_opt
       ctx->pool.push_back(q.b);
     }
     ctx->recs.clear();
+    tms[cfg] = ms;
     if (times_ms) times_ms[cfg] = ms;
     if (ms < best) { best = ms; arg = cfg; }
   }
   ctx->profiling = was;
   ctx->recs = std::move(saved);
   if (st != ACSE_OK) return st;
+  arg = keep_default(arg, best, gemm_default_cfg(prec, r * r, r * r), tms);
   ctx->tuned[{r, (int)prec}] = arg;
   *best_tile = arg;
   return ACSE_OK;
@@ -1096,13 +1108,17 @@ acse_status ensure_batch(acse_ctx c, int count, const acse_problem *probs, Batch
   return ACSE_OK;
 }
 
+int batch_cfg_default(GemmPrec prec, int count, const acse_problem *probs) {
+  int64_t rmax = 0;
+  for (int i = 0; i < count; ++i) rmax = std::max<int64_t>(rmax, probs[i].r);
+  return gemm_default_cfg(prec, (int)(rmax * rmax), (int)(rmax * rmax));
+}
+
 int batch_cfg(acse_ctx c, GemmPrec prec, int count, const acse_problem *probs, int tile) {
   if (tile >= 0) return tile;
   auto it = c->tuned_batch.find(batch_key(prec, count, probs));
   if (it != c->tuned_batch.end()) return it->second;
-  int64_t rmax = 0;
-  for (int i = 0; i < count; ++i) rmax = std::max<int64_t>(rmax, probs[i].r);
-  return gemm_default_cfg(prec, (int)(rmax * rmax), (int)(rmax * rmax));
+  return batch_cfg_default(prec, count, probs);
 }
 
 // Routes the library's launches to another stream for a scope.
@@ -1235,6 +1251,7 @@ extern "C" acse_status acse_autotune_batched(acse_ctx ctx, int32_t count, const 
   ctx->recs.clear();
   double best = 1e300;
   int arg = 0;
+  double tms[ACSE_NUM_TILE_CONFIGS] = {};
   for (int cfg = 0; cfg < ACSE_NUM_TILE_CONFIGS; ++cfg) {
     ctx->profiling = false;
     if ((st = run_batched(ctx, count, probs, prec, cfg, nullptr, nullptr, plan)) != ACSE_OK) break;
@@ -1254,12 +1271,14 @@ extern "C" acse_status acse_autotune_batched(acse_ctx ctx, int32_t count, const 
       ctx->pool.push_back(q.b);
     }
     ctx->recs.clear();
+    tms[cfg] = ms;
     if (times_ms) times_ms[cfg] = ms;
     if (ms < best) { best = ms; arg = cfg; }
   }
   ctx->profiling = was;
   ctx->recs = std::move(saved);
   if (st != ACSE_OK) return st;
+  arg = keep_default(arg, best, batch_cfg_default(prec, count, probs), tms);
   ctx->tuned_batch[batch_key(prec, count, probs)] = arg;
   *best_tile = arg;
   return ACSE_OK;
