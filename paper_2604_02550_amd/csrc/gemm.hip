@@ -162,8 +162,72 @@ __device__ __forceinline__ void gemm_tile(const GemmProb &P, int local) {
   if (nk > 0) {
     gload(kbeg);
     lstore(0);
+    // the pipelined loop below keeps the register prefetch one slab ahead of
+    // the LDS stores
+    if constexpr (NS == 2 && NP == 1) gload(kbeg + min(1, nk - 1) * BK);
     __syncthreads();
   }
+  if constexpr (NS == 2 && NP == 1) {
+    // Software-pipelined slab loop (FP64 / FP32).  The operand fragments of
+    // two MFMA steps are in registers or in flight at any time: after the
+    // MFMAs of step s, the fragments of step s + 2 are read into the same
+    // registers.  The last two steps of a slab read the first two of the next
+    // slab, so the next slab's LDS stores go between the MFMA groups, and the
+    // one barrier per slab sits before the last step, whose MFMAs then cover
+    // the latency of the first reads from the new slab.  The global loads of
+    // slab k + 2 are issued as soon as slab k + 1 is stored, so they have
+    // about one slab of MFMAs to arrive.  The loop body has no branches (the
+    // compiler's LDS wait counts are then those of the steady state): past
+    // the last slab the prefetch reloads the last slab, and the stores and
+    // reads go to the LDS buffer that is no longer read.
+    constexpr int NKK = BK / Tr::KSTEP;
+    static_assert(NKK >= 4 && NKK % 2 == 0, "pipelined loop needs an even step count >= 4");
+    T fa[2][FM], fb[2][FN];
+    auto fread = [&](int q, int b, int step) {
+#pragma unroll
+      for (int i = 0; i < FM; ++i) fa[q][i] = As[b][0][(wm0 + i * 16 + lrow) * LDK + step * Tr::KSTEP + lk];
+#pragma unroll
+      for (int j = 0; j < FN; ++j) fb[q][j] = Bs[b][0][(wn0 + j * 16 + lrow) * LDK + step * Tr::KSTEP + lk];
+    };
+    auto mma = [&](int q) {
+#pragma unroll
+      for (int i = 0; i < FM; ++i)
+#pragma unroll
+        for (int j = 0; j < FN; ++j) {
+          if constexpr (sizeof(T) == 8)
+            acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(fa[q][i], fb[q][j], acc[i][j], 0, 0, 0);
+          else
+            acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(fa[q][i], fb[q][j], acc[i][j], 0, 0, 0);
+        }
+    };
+    if (nk > 0) {
+      // same order as in the loop (steps kept apart), so that the LDS wait
+      // counts at the loop head stay those of the steady state
+      fread(0, 0, 0);
+      __builtin_amdgcn_sched_barrier(0);
+      fread(1, 0, 1);
+      __builtin_amdgcn_sched_barrier(0);
+    }
+    for (int kt = 0; kt < nk; ++kt) {
+      const int cur = kt & 1;
+#pragma unroll
+      for (int s = 0; s < NKK; ++s) {
+        mma(s & 1);
+        __builtin_amdgcn_sched_barrier(0);
+        if (s + 2 < NKK) {
+          fread(s & 1, cur, s + 2);
+        } else {
+          if (s == NKK - 2) __syncthreads();  // next slab stored; this one fully read
+          fread(s & 1, cur ^ 1, s + 2 - NKK);
+        }
+        if (s == NKK - 3) {
+          lstore(cur ^ 1);
+          gload(kbeg + min(kt + 2, nk - 1) * BK);
+        }
+        __builtin_amdgcn_sched_barrier(0);
+      }
+    }
+  } else
   for (int kt = 0; kt < nk; ++kt) {
     const int buf = NS == 2 ? (kt & 1) : 0;
     if (kt + 1 < nk) gload(kbeg + (kt + 1) * BK);
