@@ -47,6 +47,9 @@ __device__ inline double ld_ok(const double *__restrict__ p, int64_t off, bool o
   return p[ok ? off : 0];
 }
 
+// LDS bytes one workgroup may allocate on gfx950 (160 KiB per CU).
+constexpr size_t kMaxLds = 160 * 1024;
+
 // ---------------------------------------------------------------------------
 // Fold of Eq. (2): X_A blocks of the reduced Hamiltonian
 //   K_s[p,q,r,s] = (pr|qs) + (h_pr d_qs + h_qs d_pr)/(N-1)
@@ -101,25 +104,69 @@ __global__ void k_w_natural(int r, const double *__restrict__ g, const double *_
 //   Rp[(j,l),(p,s)] = W_aa[j,p,s,l] - W_ab[j,p,l,s]
 //   Rm[(j,l),(p,s)] = W_aa[j,p,s,l] + W_ab[j,p,l,s]
 //   R3[(i,l),(p,s)] = W_ab[i,p,s,l]
-// Columns >= r^2 (K padding) are written as zero.
+// Columns >= r^2 (K padding) are written as zero.  One block per (j,p): the
+// 2-RDM slabs d2aa[j,p,:,:], d2ab[j,p,:,:] (contiguous) and rows j, p of g are
+// staged in LDS (row stride r + 1), and the block writes the r x r column
+// segment (p, :) of the r rows (j, :) in contiguous runs; the block with
+// p = r - 1 also zeroes the padding columns of those rows.
+constexpr int kWphU = 4;
+
 template <class O>
-__global__ void k_w_ph(int r, int ld, const double *__restrict__ g, const double *__restrict__ d2aa,
-                       const double *__restrict__ d2ab, O Rp, O Rm, O R3) {
-  const int64_t r2 = (int64_t)r * r;
-  const int64_t e = gtid();
-  if (e >= r2 * ld) return;
-  const int col = e % ld;
-  const int row = e / ld;
-  if (col >= r2) {
-    Rp.put(e, 0.0); Rm.put(e, 0.0); R3.put(e, 0.0);
-    return;
+__global__ void __launch_bounds__(256)
+k_w_ph(int r, int ld, const double *__restrict__ g, const double *__restrict__ d2aa,
+       const double *__restrict__ d2ab, O Rp, O Rm, O R3) {
+  extern __shared__ double wph_smem[];
+  constexpr int NT = 256, U = kWphU;
+  const int r2 = r * r, RP = r + 1;
+  const int j = blockIdx.x / r, p = blockIdx.x - (blockIdx.x / r) * r;
+  double *Sa = wph_smem, *Sb = wph_smem + r * RP, *gj = wph_smem + 2 * r * RP, *gp = gj + r;
+  const int64_t src = (int64_t)blockIdx.x * r2;  // d2[j,p,:,:]
+  const int tid = threadIdx.x;
+  for (int base = 0; base < r2; base += NT * U) {
+    double va[U], vb[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int e = base + u * NT + tid;
+      va[u] = ld_ok(d2aa, src + e, e < r2);
+      vb[u] = ld_ok(d2ab, src + e, e < r2);
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int e = base + u * NT + tid;
+      if (e < r2) {
+        const int c = e / r, d = e - (e / r) * r;
+        Sa[c * RP + d] = va[u];
+        Sb[c * RP + d] = vb[u];
+      }
+    }
   }
-  const int j = row / r, l = row % r, p = col / r, s = col % r;
-  const double a = w_aa(d2aa, g, r, j, p, s, l);
-  const double b = w_ab(d2ab, g, r, j, p, l, s);
-  Rp.put(e, a - b);
-  Rm.put(e, a + b);
-  R3.put(e, w_ab(d2ab, g, r, j, p, s, l));
+  for (int e = tid; e < r; e += NT) {
+    gj[e] = g[j * r + e];
+    gp[e] = g[p * r + e];
+  }
+  __syncthreads();
+  constexpr double c23 = 2.0 / 3.0;
+  for (int e = tid; e < r2; e += NT) {
+    const int l = e / r, s = e - (e / r) * r;
+    // W_aa[j,p,s,l], W_ab[j,p,l,s], W_ab[j,p,s,l]
+    const double waa = 2.0 * Sa[s * RP + l] - c23 * (gj[s] * gp[l] - gj[l] * gp[s]);
+    const double wab = 2.0 * Sb[l * RP + s] - c23 * gj[l] * gp[s];
+    const double w3 = 2.0 * Sb[s * RP + l] - c23 * gj[s] * gp[l];
+    const int64_t o = ((int64_t)j * r + l) * ld + (int64_t)p * r + s;
+    Rp.put(o, waa - wab);
+    Rm.put(o, waa + wab);
+    R3.put(o, w3);
+  }
+  if (p == r - 1) {
+    const int pad = ld - r2;
+    for (int e = tid; e < r * pad; e += NT) {
+      const int l = e / pad, c = e - (e / pad) * pad;
+      const int64_t o = ((int64_t)j * r + l) * ld + r2 + c;
+      Rp.put(o, 0.0);
+      Rm.put(o, 0.0);
+      R3.put(o, 0.0);
+    }
+  }
 }
 
 // pp A operands, packed by the pair symmetries of the 2-RDM blocks (the factor
@@ -515,50 +562,98 @@ k_sandwich(int r, const double *__restrict__ Xaa, const double *__restrict__ Xab
 //   B_A [(k,l), (r<s)] = B_ab[k,l,r,s] - B_ab[k,l,s,r]
 // One block per row (k,l): the natural B rows are staged in LDS.
 // ---------------------------------------------------------------------------
-template <class O>
-__global__ void __launch_bounds__(256)
+// MIR: the mirrored H_ab row (l,k) is first copied to LDS so that its
+// transposed read H_ab[l,k,s,r] is an LDS read, not a stride-r global gather
+// (three r x (r+1) LDS arrays instead of two).  LDS rows have stride r + 1 so
+// the transposed reads are conflict-free.  The element loops issue the global
+// loads of kG2U iterations before using any (a block holds one row, so its
+// loads would otherwise wait one latency per iteration).
+constexpr int kG2U = 4;
+
+template <class O, bool MIR>
+__global__ void __launch_bounds__(512)
 k_g2(int r, int ld_lt, int ld_le, const double *__restrict__ Aaa, const double *__restrict__ Aab,
      const double *__restrict__ Haa, const double *__restrict__ Hab, const double *__restrict__ f,
      double *__restrict__ G2aa, double *__restrict__ G2ab, O Baa, O BS, O BA) {
   extern __shared__ double g2_smem[];
-  const int r2 = r * r;
+  constexpr int NT = 512, U = kG2U;
+  const int r2 = r * r, RP = r + 1;
   const int row = blockIdx.x;
   const int k = row / r, l = row - (row / r) * r;
   const int64_t nat0 = (int64_t)row * r2, mir0 = ((int64_t)l * r + k) * r2;
-  double *ba = g2_smem, *bb = g2_smem + r2;
-  for (int e = threadIdx.x; e < r2; e += 256) {
-    const int rr = e / r, s = e - (e / r) * r;
-    double gaa = Haa[nat0 + e] - Haa[mir0 + e];
-    if (l == s) gaa += f[k * r + rr];
-    if (l == rr) gaa -= f[k * r + s];
-    if (k == s) gaa -= f[l * r + rr];
-    if (k == rr) gaa += f[l * r + s];
-    double gab = Hab[nat0 + e] + Hab[mir0 + (int64_t)s * r + rr];
-    if (l == s) gab += f[k * r + rr];
-    if (k == rr) gab += f[l * r + s];
-    G2aa[nat0 + e] = gaa;
-    G2ab[nat0 + e] = gab;
-    ba[e] = Aaa[nat0 + e] - gaa;
-    bb[e] = Aab[nat0 + e] - gab;
+  double *ba = g2_smem, *bb = g2_smem + r * RP, *mh = g2_smem + 2 * r * RP;
+  const int tid = threadIdx.x;
+  if constexpr (MIR) {
+    for (int base = 0; base < r2; base += NT * U) {
+      double v[U];
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int e = base + u * NT + tid;
+        v[u] = ld_ok(Hab, mir0 + e, e < r2);
+      }
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int e = base + u * NT + tid;
+        if (e < r2) {
+          const int x = e / r, y = e - (e / r) * r;
+          mh[x * RP + y] = v[u];
+        }
+      }
+    }
+    __syncthreads();
+  }
+  for (int base = 0; base < r2; base += NT * U) {
+    double hn[U], hm[U], bn[U], bm[U], an[U], aab[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int e = base + u * NT + tid;
+      const bool ok = e < r2;
+      const int ee = ok ? e : 0;
+      const int rr = ee / r, s = ee - (ee / r) * r;
+      hn[u] = ld_ok(Haa, nat0 + e, ok);
+      hm[u] = ld_ok(Haa, mir0 + e, ok);
+      bn[u] = ld_ok(Hab, nat0 + e, ok);
+      if constexpr (!MIR) bm[u] = ld_ok(Hab, mir0 + (int64_t)s * r + rr, ok);
+      an[u] = ld_ok(Aaa, nat0 + e, ok);
+      aab[u] = ld_ok(Aab, nat0 + e, ok);
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int e = base + u * NT + tid;
+      if (e >= r2) continue;
+      const int rr = e / r, s = e - (e / r) * r;
+      double gaa = hn[u] - hm[u];
+      if (l == s) gaa += f[k * r + rr];
+      if (l == rr) gaa -= f[k * r + s];
+      if (k == s) gaa -= f[l * r + rr];
+      if (k == rr) gaa += f[l * r + s];
+      double gab = bn[u] + (MIR ? mh[s * RP + rr] : bm[u]);
+      if (l == s) gab += f[k * r + rr];
+      if (k == rr) gab += f[l * r + s];
+      G2aa[nat0 + e] = gaa;
+      G2ab[nat0 + e] = gab;
+      ba[rr * RP + s] = an[u] - gaa;
+      bb[rr * RP + s] = aab[u] - gab;
+    }
   }
   __syncthreads();
   const int nle = npair_le(r), nlt = npair_lt(r);
-  for (int q = threadIdx.x; q < ld_le; q += 256) {
+  for (int q = tid; q < ld_le; q += NT) {
     double v = 0.0;
     if (q < nle) {
       int a, b;
       unpair_le(r, q, a, b);
-      v = bb[a * r + b] + bb[b * r + a];
+      v = bb[a * RP + b] + bb[b * RP + a];
     }
     BS.put((int64_t)row * ld_le + q, v);
   }
-  for (int q = threadIdx.x; q < ld_lt; q += 256) {
+  for (int q = tid; q < ld_lt; q += NT) {
     double va = 0.0, vb = 0.0;
     if (q < nlt) {
       int a, b;
       unpair_lt(r, q, a, b);
-      va = ba[a * r + b] - ba[b * r + a];
-      vb = bb[a * r + b] - bb[b * r + a];
+      va = ba[a * RP + b] - ba[b * RP + a];
+      vb = bb[a * RP + b] - bb[b * RP + a];
     }
     Baa.put((int64_t)row * ld_lt + q, va);
     BA.put((int64_t)row * ld_lt + q, vb);
@@ -652,6 +747,98 @@ k_assemble(int r, const double *__restrict__ g, const double *__restrict__ t,
       Sab[out] = zab + gt_ab - e2;
     }
     __syncthreads();
+  }
+}
+
+// Whole-slab form of the same assembly (r <= 81), one block per unordered pair
+// {i <= j} writing S[i,j,:,:] and S[j,i,:,:].  With E1 = P+ + P- and
+// Y = P+ - P- - E3, the ph terms of the two slabs are
+//   slab (i,j): e1 = D[k,l] - D[l,k],     e2 = Y[i,j,k,l] + Y[j,i,l,k]
+//   slab (j,i): e1 = -(D[k,l] - D[l,k]),  e2 = Y[j,i,k,l] + Y[i,j,l,k]
+// with D[k,l] = E1[i,j,k,l] - E1[j,i,k,l].  The block reads the six input
+// slabs X[i,j,:,:], X[j,i,:,:] (contiguous r^2 runs, each read once overall),
+// keeps D and the two Y slabs in LDS (row stride r + 1, so the transposed
+// reads are conflict-free) together with rows i, j of g and t, and writes both
+// output slabs in contiguous runs.
+constexpr int kAsmThreads = 512;
+constexpr int kAsmU = 4;  // loop iterations whose global loads are issued together
+
+__global__ void __launch_bounds__(kAsmThreads)
+k_assemble_slab(int r, const double *__restrict__ g, const double *__restrict__ t,
+                const double *__restrict__ Zaa, const double *__restrict__ ZS, const double *__restrict__ ZA,
+                const double *__restrict__ Pp, const double *__restrict__ Pm,
+                const double *__restrict__ E3, double *__restrict__ Saa, double *__restrict__ Sab) {
+  extern __shared__ double asm_smem[];
+  int i = 0, rem = blockIdx.x;
+  while (rem >= r - i) { rem -= r - i; ++i; }
+  const int j = i + rem;
+  const int r2 = r * r, RP = r + 1, SL = r * RP;
+  double *D = asm_smem, *Y0 = asm_smem + SL, *Y1 = asm_smem + 2 * SL;
+  double *gi = asm_smem + 3 * SL, *gj = gi + r, *ti = gj + r, *tj = ti + r;
+  const int64_t s0 = ((int64_t)i * r + j) * r2, s1 = ((int64_t)j * r + i) * r2;
+  constexpr int U = kAsmU;
+  const int tid = threadIdx.x;
+  for (int base = 0; base < r2; base += kAsmThreads * U) {
+    double p0[U], m0[U], x0[U], p1[U], m1[U], x1[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int e = base + u * kAsmThreads + tid;
+      const bool ok = e < r2;
+      p0[u] = ld_ok(Pp, s0 + e, ok); m0[u] = ld_ok(Pm, s0 + e, ok); x0[u] = ld_ok(E3, s0 + e, ok);
+      p1[u] = ld_ok(Pp, s1 + e, ok); m1[u] = ld_ok(Pm, s1 + e, ok); x1[u] = ld_ok(E3, s1 + e, ok);
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int e = base + u * kAsmThreads + tid;
+      if (e >= r2) continue;
+      const int k = e / r, l = e - (e / r) * r;
+      D[k * RP + l] = (p0[u] + m0[u]) - (p1[u] + m1[u]);
+      Y0[k * RP + l] = (p0[u] - m0[u]) - x0[u];
+      Y1[k * RP + l] = (p1[u] - m1[u]) - x1[u];
+    }
+  }
+  for (int e = threadIdx.x; e < r; e += kAsmThreads) {
+    gi[e] = g[i * r + e]; gj[e] = g[j * r + e];
+    ti[e] = t[i * r + e]; tj[e] = t[j * r + e];
+  }
+  __syncthreads();
+  const int64_t zs0 = (int64_t)blockIdx.x * r2;                        // Z_S row (i<=j)
+  const int64_t za0 = i < j ? (int64_t)pair_lt(r, i, j) * r2 : 0;      // Z_aa, Z_A row (i<j)
+  const bool off = i != j;
+  for (int base = 0; base < r2; base += kAsmThreads * U) {
+    double vzs[U], vzaa[U], vza[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int e = base + u * kAsmThreads + tid;
+      const bool ok = e < r2;
+      vzs[u] = ld_ok(ZS, zs0 + e, ok);
+      vzaa[u] = ld_ok(Zaa, za0 + e, ok);
+      vza[u] = ld_ok(ZA, za0 + e, ok);
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int e = base + u * kAsmThreads + tid;
+      if (e >= r2) continue;
+      const int k = e / r, l = e - (e / r) * r;
+      const double zs = vzs[u];
+      const double zaa = off ? vzaa[u] : 0.0, za = off ? vza[u] : 0.0;
+      const double e1 = D[k * RP + l] - D[l * RP + k];
+      // slab (a, b) = (i, j)
+      {
+        const double gt_aa = gi[l] * tj[k] - gj[l] * ti[k] - gi[k] * tj[l] + gj[k] * ti[l];
+        const double gt_ab = gj[l] * ti[k] + gi[k] * tj[l];
+        const double e2 = Y0[k * RP + l] + Y1[l * RP + k];
+        Saa[s0 + e] = zaa - gt_aa - e1;
+        Sab[s0 + e] = 0.5 * (zs + za) + gt_ab - e2;
+      }
+      if (off) {  // slab (a, b) = (j, i)
+        const double gt_aa = gj[l] * ti[k] - gi[l] * tj[k] - gj[k] * ti[l] + gi[k] * tj[l];
+        const double gt_ab = gi[l] * tj[k] + gj[k] * ti[l];
+        const double e2 = Y1[k * RP + l] + Y0[l * RP + k];
+        Saa[s1 + e] = -zaa - gt_aa + e1;
+        Sab[s1 + e] = 0.5 * (zs - za) + gt_ab - e2;
+      }
+    }
   }
 }
 
@@ -1081,9 +1268,14 @@ template <> OutBF16x3 make_out<OutBF16x3>(const OperandRef &o) {
 hipError_t launch_w_ph(GemmPrec prec, int r, int ld, const double *g, const double *d2aa,
                        const double *d2ab, const OperandRef &Rp, const OperandRef &Rm,
                        const OperandRef &R3, hipStream_t s) {
-  const int64_t n = (int64_t)r * r * ld;
-  ACSE_DISPATCH_OUT(prec, hipLaunchKernelGGL((k_w_ph<O>), grid_for(n), dim3(256), 0, s, r, ld, g, d2aa,
-                                             d2ab, make_out<O>(Rp), make_out<O>(Rm), make_out<O>(R3)));
+  const size_t lds = ((size_t)2 * r * (r + 1) + 2 * (size_t)r) * sizeof(double);
+  ACSE_DISPATCH_OUT(prec, {
+    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(&k_w_ph<O>),
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL((k_w_ph<O>), dim3((unsigned)(r * r)), dim3(256), lds, s, r, ld, g, d2aa, d2ab,
+                       make_out<O>(Rp), make_out<O>(Rm), make_out<O>(R3));
+  });
   return hipGetLastError();
 }
 
@@ -1216,26 +1408,44 @@ hipError_t launch_mode(GemmPrec prec, const ModeArgs &m, const OperandRef &out, 
 hipError_t launch_g2(GemmPrec prec, int r, const double *Aaa, const double *Aab, const double *Haa,
                      const double *Hab, const double *f, double *G2aa, double *G2ab,
                      const OperandRef &Baa, const OperandRef &BS, const OperandRef &BA, hipStream_t s) {
-  const size_t lds = (size_t)2 * r * r * sizeof(double);
+  const size_t lds2 = (size_t)2 * r * (r + 1) * sizeof(double);
+  const size_t lds3 = lds2 + (size_t)r * (r + 1) * sizeof(double);
+  const bool mir = lds3 <= kMaxLds;
+  const size_t lds = mir ? lds3 : lds2;
   const int ld_lt = (int)ld_pair_lt(r), ld_le = (int)ld_pair_le(r);
-  ACSE_DISPATCH_OUT(prec, {
-    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(&k_g2<O>),
+  auto go = [&](auto kern, auto tag) -> hipError_t {
+    using O = decltype(tag);
+    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(kern),
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL((k_g2<O>), dim3((unsigned)(r * r)), dim3(256), lds, s, r, ld_lt, ld_le, Aaa, Aab,
-                       Haa, Hab, f, G2aa, G2ab, make_out<O>(Baa), make_out<O>(BS), make_out<O>(BA));
-  });
-  return hipGetLastError();
+    hipLaunchKernelGGL(kern, dim3((unsigned)(r * r)), dim3(512), lds, s, r, ld_lt, ld_le, Aaa, Aab, Haa,
+                       Hab, f, G2aa, G2ab, make_out<O>(Baa), make_out<O>(BS), make_out<O>(BA));
+    return hipGetLastError();
+  };
+  if (prec == GEMM_F64)
+    return mir ? go(k_g2<OutF64, true>, OutF64{}) : go(k_g2<OutF64, false>, OutF64{});
+  if (prec == GEMM_F32)
+    return mir ? go(k_g2<OutF32, true>, OutF32{}) : go(k_g2<OutF32, false>, OutF32{});
+  return mir ? go(k_g2<OutBF16x3, true>, OutBF16x3{}) : go(k_g2<OutBF16x3, false>, OutBF16x3{});
 }
 
 hipError_t launch_assemble(int r, const double *g, const double *t, const double *Zaa,
                            const double *ZS, const double *ZA, const double *Pp, const double *Pm,
                            const double *E3, double *Saa, double *Sab, hipStream_t s) {
+  const unsigned npairs = (unsigned)(r * (r + 1) / 2);
+  const size_t slab_lds = ((size_t)3 * r * (r + 1) + 4 * (size_t)r) * sizeof(double);
+  if (slab_lds <= kMaxLds) {
+    hipError_t err = hipFuncSetAttribute(reinterpret_cast<const void *>(&k_assemble_slab),
+                                         hipFuncAttributeMaxDynamicSharedMemorySize, (int)slab_lds);
+    if (err != hipSuccess) return err;
+    hipLaunchKernelGGL(k_assemble_slab, dim3(npairs), dim3(kAsmThreads), slab_lds, s, r, g, t, Zaa, ZS, ZA,
+                       Pp, Pm, E3, Saa, Sab);
+    return hipGetLastError();
+  }
   const size_t lds = (size_t)6 * (kKC * r + r * (kKC + 1)) * sizeof(double);
   hipError_t err = hipFuncSetAttribute(reinterpret_cast<const void *>(&k_assemble),
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   if (err != hipSuccess) return err;
-  const unsigned npairs = (unsigned)(r * (r + 1) / 2);
   hipLaunchKernelGGL(k_assemble, dim3(npairs, (unsigned)((r + kKC - 1) / kKC)), dim3(256), lds, s, r, g,
                      t, Zaa, ZS, ZA, Pp, Pm, E3, Saa, Sab);
   return hipGetLastError();
