@@ -21,18 +21,23 @@ typedef double d4 __attribute__((ext_vector_type(4)));
 typedef float f4 __attribute__((ext_vector_type(4)));
 typedef __bf16 bf8 __attribute__((ext_vector_type(8)));
 
-// PAD: LDS row padding in elements.  FP64/FP32 fragment reads take one element
-// per lane from 16 consecutive rows, so an odd row stride puts the 16 rows in
-// distinct banks (the staging stores then split into element-size pieces).
+// PAD: LDS row padding in elements.  Fragment reads take one element per lane
+// from 16 consecutive rows (and 4 consecutive k).  FP64: a 64-bit read serves
+// 32 lanes (16 rows x 2 k) per pass, and a row stride of BK + 2 doubles puts
+// them on 32 distinct bank pairs (BK + 1 leaves one 2-way conflict per pass);
+// the rows also stay 16-byte aligned for whole-chunk staging stores.  FP32: a
+// row stride of BK + 4 floats keeps the rows 16-byte aligned (whole-chunk
+// stores); the counters still show some conflicts on its 32-bit reads, with
+// the same product time as the odd stride BK + 1.
 struct TrF64 {
   using T = double;
   using Acc = d4;
-  static constexpr int NPLANE = 1, VEC = 2, PAD = 1, KSTEP = 4;
+  static constexpr int NPLANE = 1, VEC = 2, PAD = 2, KSTEP = 4;
 };
 struct TrF32 {
   using T = float;
   using Acc = f4;
-  static constexpr int NPLANE = 1, VEC = 4, PAD = 1, KSTEP = 4;
+  static constexpr int NPLANE = 1, VEC = 4, PAD = 4, KSTEP = 4;
 };
 struct TrBF16x3 {
   using T = __bf16;

@@ -67,6 +67,12 @@ hipError_t launch_zero_kpad(GemmPrec prec, int r, int ld, const OperandRef &o, h
 hipError_t launch_f(int r, const double *Aaa, const double *Aab, const double *g, double *part,
                     double *f, hipStream_t s);
 hipError_t launch_mode(GemmPrec prec, const ModeArgs &m, const OperandRef &out, hipStream_t s);
+// ph A operands L+, L-, L3 (rows (k,i), K (p,s), leading dimension ld, K
+// padding zeroed) in one pass over X_aa, X_ab; r <= kLopsMaxR (the register
+// budget of two waves per SIMD; larger r use three one-index transforms).
+constexpr int kLopsMaxR = 56;
+hipError_t launch_lops(GemmPrec prec, int r, int ld, const double *g, const double *Xaa, const double *Xab,
+                       const OperandRef &Lp, const OperandRef &Lm, const OperandRef &L3, hipStream_t s);
 // out[k,l,:,:] = alpha g X[k,l,:,:] g for both blocks (g symmetric, r <= 64;
 // hipErrorInvalidValue above).
 constexpr int kSandwichMaxR = 64;

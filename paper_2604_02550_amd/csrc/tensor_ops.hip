@@ -441,6 +441,139 @@ k_mode(ModeArgs m, O out, int npanels) {
 }
 
 // ---------------------------------------------------------------------------
+// The three ph A operands in one pass over the two input blocks (r <= 56):
+//   L+[(k,i),(p,s)] = sum_r g[i,r] (X_aa + X_ab)[k,p,r,s]
+//   L-[(k,i),(p,s)] = sum_r g[i,r] (X_aa - X_ab)[k,p,r,s]
+//   L3[(k,j),(p,s)] = sum_r g[j,r] X_ab[k,p,s,r]
+// i.e. per slab (k,p) three r x r products with g.  Persistent blocks walk the
+// r^2 slabs; the two input slabs are staged in LDS (rows r.., columns r.. of
+// the staging area zero; the next slab's loads are in flight in registers
+// during the MFMAs), g is the FP64 MFMA A operand held in registers (wave w:
+// output rows 16w..16w+15), and the output rows (k,i) get the 16-column runs
+// (p, s).  The block that handles p = r - 1 also zeroes the K padding of the
+// r rows (k, .) of all three operands.  LDS row stride: >= 4 KS and = 2 mod 4,
+// which keeps the transposed reads of X_ab conflict-free.
+// ---------------------------------------------------------------------------
+static inline int lops_rp(int ks) { return 4 * ks + 2; }
+
+template <class O, int KS>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2)))
+k_lops(int r, int ld, int rp, const double *__restrict__ g, const double *__restrict__ Xaa,
+       const double *__restrict__ Xab, O Lp, O Lm, O L3, int nslab) {
+  constexpr int CB = (4 * KS + 15) / 16;   // 16-column output blocks (and 16-row blocks)
+  constexpr int NR = CB * 16;              // staged rows (>= 4 KS, >= r)
+  constexpr int PF = (4 * KS * 4 * KS + 255) / 256;  // prefetched elements per thread per slab
+  extern __shared__ double lops_smem[];
+  double *SA = lops_smem, *SB = lops_smem + NR * rp;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int lr = lane & 15, lk = lane >> 4;
+  const int r2 = r * r;
+  double afr[KS];
+#pragma unroll
+  for (int ks = 0; ks < KS; ++ks) {
+    const int x = wave * 16 + lr, y = ks * 4 + lk;
+    const bool ok = x < r && y < r;
+    const double v = ld_ok(g, (int64_t)x * r + y, ok);
+    afr[ks] = ok ? v : 0.0;
+  }
+  for (int e = tid; e < 2 * NR * rp; e += 256) lops_smem[e] = 0.0;
+  __syncthreads();
+  double va[PF], vb[PF];
+  auto fetch = [&](int q) {
+    const int64_t base = (int64_t)q * r2;
+#pragma unroll
+    for (int u = 0; u < PF; ++u) {
+      const int e = tid + u * 256;
+      va[u] = ld_ok(Xaa, base + e, e < r2);
+      vb[u] = ld_ok(Xab, base + e, e < r2);
+    }
+  };
+  auto deposit = [&]() {
+#pragma unroll
+    for (int u = 0; u < PF; ++u) {
+      const int e = tid + u * 256;
+      if (e < r2) {
+        const int row = e / r, col = e - (e / r) * r;
+        SA[row * rp + col] = va[u];
+        SB[row * rp + col] = vb[u];
+      }
+    }
+  };
+  int q = blockIdx.x;
+  fetch(q);
+  deposit();
+  __syncthreads();
+  for (;;) {
+    const int qn = q + (int)gridDim.x;
+    const bool more = qn < nslab;
+    if (more) fetch(qn);
+    const int k = q / r, p = q - (q / r) * r;
+    // accumulator item v of lane l: output row 16 wave + l/16 + 4v, column 16 cb + l%16
+    auto store = [&](const mode_d4 *acc, O &out) {
+#pragma unroll
+      for (int cb = 0; cb < CB; ++cb) {
+        const int sc = cb * 16 + lr;
+        if (sc < r) {
+#pragma unroll
+          for (int v = 0; v < 4; ++v) {
+            const int i = wave * 16 + lk + 4 * v;
+            if (i < r) out.put(((int64_t)k * r + i) * ld + (int64_t)p * r + sc, acc[cb][v]);
+          }
+        }
+      }
+    };
+    {  // L+ and L- (two passes over the slab keep fewer accumulators live)
+      mode_d4 ap[CB], am[CB];
+#pragma unroll
+      for (int cb = 0; cb < CB; ++cb) {
+        ap[cb] = mode_d4{0.0, 0.0, 0.0, 0.0};
+        am[cb] = ap[cb];
+      }
+#pragma unroll
+      for (int ks = 0; ks < KS; ++ks) {
+        const int kr = ks * 4 + lk;
+#pragma unroll
+        for (int cb = 0; cb < CB; ++cb) {
+          const double xa = SA[kr * rp + cb * 16 + lr], xb = SB[kr * rp + cb * 16 + lr];
+          ap[cb] = __builtin_amdgcn_mfma_f64_16x16x4f64(afr[ks], xa + xb, ap[cb], 0, 0, 0);
+          am[cb] = __builtin_amdgcn_mfma_f64_16x16x4f64(afr[ks], xa - xb, am[cb], 0, 0, 0);
+        }
+      }
+      store(ap, Lp);
+      store(am, Lm);
+    }
+    {  // L3
+      mode_d4 a3[CB];
+#pragma unroll
+      for (int cb = 0; cb < CB; ++cb) a3[cb] = mode_d4{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+      for (int ks = 0; ks < KS; ++ks) {
+        const int kr = ks * 4 + lk;
+#pragma unroll
+        for (int cb = 0; cb < CB; ++cb)
+          a3[cb] = __builtin_amdgcn_mfma_f64_16x16x4f64(afr[ks], SB[(cb * 16 + lr) * rp + kr], a3[cb], 0, 0, 0);
+      }
+      store(a3, L3);
+    }
+    if (p == r - 1) {
+      const int pad = ld - r2;
+      for (int e = tid; e < r * pad; e += 256) {
+        const int i = e / pad, c = e - (e / pad) * pad;
+        const int64_t o = ((int64_t)k * r + i) * ld + r2 + c;
+        Lp.put(o, 0.0);
+        Lm.put(o, 0.0);
+        L3.put(o, 0.0);
+      }
+    }
+    if (!more) break;
+    __syncthreads();  // every wave is done with the staged slab
+    deposit();
+    __syncthreads();
+    q = qn;
+  }
+}
+
+// ---------------------------------------------------------------------------
 // Two-sided transform of r x r slices:  out[k,l,:,:] = alpha g X[k,l,:,:] g
 // (g symmetric) for the 2 r^2 slices of Xaa and Xab, i.e. C^T_kl = 4/3 g G2_kl g.
 // One pass over the data instead of two one-index transforms: per slice,
@@ -1300,6 +1433,50 @@ hipError_t launch_zero_kpad(GemmPrec prec, int r, int ld, const OperandRef &o, h
   ACSE_DISPATCH_OUT(prec, hipLaunchKernelGGL((k_zero_kpad<O>), grid_for(n), dim3(256), 0, s, r, ld,
                                              make_out<O>(o)));
   return hipGetLastError();
+}
+
+template <class O, int KS>
+static hipError_t launch_lops_t(int r, int ld, const double *g, const double *Xaa, const double *Xab,
+                                O Lp, O Lm, O L3, hipStream_t s) {
+  static int resident = 0;  // blocks the device holds at once
+  constexpr int NR = ((4 * KS + 15) / 16) * 16;
+  const int rp = lops_rp(KS);
+  const size_t lds = (size_t)2 * NR * rp * sizeof(double);
+  const void *fn = reinterpret_cast<const void *>(&k_lops<O, KS>);
+  if (resident == 0) {
+    int dev = 0, cus = 0, per_cu = 0;
+    hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e == hipSuccess) e = hipGetDevice(&dev);
+    if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    if (e == hipSuccess) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, 256, lds);
+    if (e != hipSuccess) return e;
+    resident = cus * std::max(per_cu, 1);
+  }
+  const int nslab = r * r;
+  hipLaunchKernelGGL((k_lops<O, KS>), dim3(std::min(nslab, resident)), dim3(256), lds, s, r, ld, rp, g, Xaa,
+                     Xab, Lp, Lm, L3, nslab);
+  return hipGetLastError();
+}
+
+template <class O>
+static hipError_t launch_lops_o(int r, int ld, const double *g, const double *Xaa, const double *Xab, O Lp,
+                                O Lm, O L3, hipStream_t s) {
+  switch ((r + 3) / 4) {
+#define ACSE_LOPS(K) \
+    case K: return launch_lops_t<O, K>(r, ld, g, Xaa, Xab, Lp, Lm, L3, s);
+    ACSE_LOPS(1) ACSE_LOPS(2) ACSE_LOPS(3) ACSE_LOPS(4) ACSE_LOPS(5) ACSE_LOPS(6) ACSE_LOPS(7)
+    ACSE_LOPS(8) ACSE_LOPS(9) ACSE_LOPS(10) ACSE_LOPS(11) ACSE_LOPS(12) ACSE_LOPS(13) ACSE_LOPS(14)
+#undef ACSE_LOPS
+    default: return hipErrorInvalidValue;
+  }
+}
+
+hipError_t launch_lops(GemmPrec prec, int r, int ld, const double *g, const double *Xaa, const double *Xab,
+                       const OperandRef &Lp, const OperandRef &Lm, const OperandRef &L3, hipStream_t s) {
+  if (r < 2 || r > kLopsMaxR) return hipErrorInvalidValue;
+  ACSE_DISPATCH_OUT(prec, return launch_lops_o(r, ld, g, Xaa, Xab, make_out<O>(Lp), make_out<O>(Lm),
+                                               make_out<O>(L3), s));
+  return hipSuccess;
 }
 
 hipError_t launch_f(int r, const double *Aaa, const double *Aab, const double *g, double *part,
