@@ -99,7 +99,16 @@ typedef struct {
                              four of its spatial indices are active (the "all active"
                              option of the method section); the norm is taken first. */
   int32_t tile;           /* GEMM tile configuration, -1 = autotuned default */
+  int32_t flags;          /* bitwise OR of ACSE_FLAG_* (0 = none) */
 } acse_options;
+
+/* acse_options.flags: run the general-size transform kernels at every r (the
+ * one-index transforms for the ph A operands and for the g G2 g product, the
+ * G2 kernel without the mirrored-row staging and the row-chunked assembly),
+ * which otherwise serve only the sizes the faster kernels do not cover
+ * (r > 56, r > 64, r > 81).  Same results up to rounding order; meant for
+ * verifying those kernels at small r.  Other bits are an ACSE_ERR_ARG. */
+#define ACSE_FLAG_GENERAL_KERNELS 1
 
 /* Creates a context on HIP device `device`, ordering work on `hip_stream`
  * (a hipStream_t; NULL = the default stream), with workspace for problems up

@@ -50,7 +50,11 @@ class ProfileData(ctypes.Structure):
 
 
 class Options(ctypes.Structure):
-    _fields_ = [("precision", ctypes.c_int32), ("active", ctypes.c_void_p), ("tile", ctypes.c_int32)]
+    _fields_ = [("precision", ctypes.c_int32), ("active", ctypes.c_void_p), ("tile", ctypes.c_int32),
+                ("flags", ctypes.c_int32)]
+
+
+FLAG_GENERAL_KERNELS = 1
 
 
 _P = ctypes.c_void_p
@@ -167,14 +171,14 @@ class Context:
         return prob, t
 
     @staticmethod
-    def options(precision="fp64", active=None, tile=-1):
+    def options(precision="fp64", active=None, tile=-1, flags=0):
         prec = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
         keep = None
         act = None
         if active is not None:
             keep = (ctypes.c_uint8 * len(active))(*[1 if a else 0 for a in active])
             act = ctypes.cast(keep, ctypes.c_void_p)
-        o = Options(prec, act, int(tile))
+        o = Options(prec, act, int(tile), int(flags))
         o._keep = keep
         return o
 
@@ -184,23 +188,23 @@ class Context:
                                        _ptr(R_ab), ctypes.byref(n2) if want_norm else None))
         return n2.value
 
-    def residual(self, h, V, d1, d2aa, d2ab, n_alpha, precision="fp64", tile=-1):
+    def residual(self, h, V, d1, d2aa, d2ab, n_alpha, precision="fp64", tile=-1, flags=0):
         """R_aa, R_ab (device, float64) and ||R||^2 of Eq. (4)."""
         prob, keep = self.problem(h, V, d1, d2aa, d2ab, n_alpha)
         r = prob.r
         R_aa = torch.empty((r, r, r, r), dtype=torch.float64, device=self.device)
         R_ab = torch.empty_like(R_aa)
-        n2 = self.residual_raw(prob, self.options(precision, None, tile), R_aa, R_ab)
+        n2 = self.residual_raw(prob, self.options(precision, None, tile, flags), R_aa, R_ab)
         return R_aa, R_ab, n2
 
-    def update_map(self, h, V, d1, d2aa, d2ab, n_alpha, X_aa, X_ab, precision="fp64", tile=-1):
+    def update_map(self, h, V, d1, d2aa, d2ab, n_alpha, X_aa, X_ab, precision="fp64", tile=-1, flags=0):
         """U = 1/2 <[a+a+aa, sum X a+a+aa]> for anti-Hermitian X (Eq. (9))."""
         prob, keep = self.problem(h, V, d1, d2aa, d2ab, n_alpha)
         X_aa, X_ab = _dev(X_aa, self.device), _dev(X_ab, self.device)
         U_aa = torch.empty_like(X_aa)
         U_ab = torch.empty_like(X_ab)
         self._check(_lib.acse_update_map(self._h, ctypes.byref(prob),
-                                         ctypes.byref(self.options(precision, None, tile)),
+                                         ctypes.byref(self.options(precision, None, tile, flags)),
                                          _ptr(X_aa), _ptr(X_ab), _ptr(U_aa), _ptr(U_ab)))
         return U_aa, U_ab
 
@@ -225,7 +229,7 @@ class Context:
         return e.value, n2.value
 
     def step(self, h, V, d1, d2aa, d2ab, n_alpha, eps=1e-3, precision="fp64", active=None,
-             tile=-1, return_ru=False):
+             tile=-1, return_ru=False, flags=0):
         """One Euler step of Eq. (9) on device copies; returns a dict with the new
         d1, d2aa, d2ab, the energy after the step and ||R||^2 before it."""
         prob, t = self.problem(h, V, d1, d2aa, d2ab, n_alpha)
@@ -234,7 +238,7 @@ class Context:
         bufs = [None] * 4
         if return_ru:
             bufs = [torch.empty((r, r, r, r), dtype=torch.float64, device=self.device) for _ in range(4)]
-        E, n2 = self.step_raw(prob, eps, self.options(precision, active, tile), *bufs)
+        E, n2 = self.step_raw(prob, eps, self.options(precision, active, tile, flags), *bufs)
         if return_ru:
             extra = dict(R_aa=bufs[0], R_ab=bufs[1], U_aa=bufs[2], U_ab=bufs[3])
         return dict(d1=t[2], d2aa=t[3], d2ab=t[4], energy=E, norm2=n2, **extra)
@@ -244,13 +248,14 @@ class Context:
                                            _ptr(Rbar_aa), _ptr(Rbar_ab), _ptr(h_bar), _ptr(V_bar),
                                            _ptr(d1_bar), _ptr(d2aa_bar), _ptr(d2ab_bar)))
 
-    def residual_vjp(self, h, V, d1, d2aa, d2ab, n_alpha, Rbar_aa, Rbar_ab, precision="fp64", tile=-1):
+    def residual_vjp(self, h, V, d1, d2aa, d2ab, n_alpha, Rbar_aa, Rbar_ab, precision="fp64", tile=-1,
+                     flags=0):
         """Cotangents (h, V, d1, d2aa, d2ab) of <Rbar, R> for the residual of Eq. (4),
         projected onto the symmetry subspace of each input."""
         prob, keep = self.problem(h, V, d1, d2aa, d2ab, n_alpha)
         rb = [_dev(x, self.device) for x in (Rbar_aa, Rbar_ab)]
         out = [torch.empty_like(x) for x in keep]
-        self.residual_vjp_raw(prob, self.options(precision, None, tile), *rb, *out)
+        self.residual_vjp_raw(prob, self.options(precision, None, tile, flags), *rb, *out)
         return tuple(out)
 
     def residual_batched_raw(self, probs, opts, R_aa, R_ab, want_norm=True):
@@ -274,7 +279,7 @@ class Context:
                                                times))
         return best.value, list(times)
 
-    def residual_batched(self, instances, precision="fp64", tile=-1):
+    def residual_batched(self, instances, precision="fp64", tile=-1, flags=0):
         """instances: sequence of dicts with h, V, gamma, d2aa, d2ab, N.  One
         batched call; returns [(R_aa, R_ab, norm2)] in input order."""
         probs, keep, outs = [], [], []
@@ -285,7 +290,7 @@ class Context:
             r = prob.r
             outs.append([torch.empty((r, r, r, r), dtype=torch.float64, device=self.device)
                          for _ in range(2)])
-        n2 = self.residual_batched_raw(probs, self.options(precision, None, tile),
+        n2 = self.residual_batched_raw(probs, self.options(precision, None, tile, flags),
                                        [o[0] for o in outs], [o[1] for o in outs])
         return [(o[0], o[1], v) for o, v in zip(outs, n2)]
 

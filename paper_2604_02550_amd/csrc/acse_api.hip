@@ -70,6 +70,8 @@ struct acse_ctx_s {
   double ms[ACSE_NUM_STAGES] = {};
   int64_t count[ACSE_NUM_STAGES] = {};
   std::map<std::pair<int, int>, int> tuned;  // (r, precision) -> tile configuration
+  // ACSE_FLAG_GENERAL_KERNELS of the options of the call in progress (set by validate)
+  bool general = false;
   // batched residual: one workspace per instance, sized for its own r
   void *bbase = nullptr;
   int64_t bbytes = 0;
@@ -189,7 +191,9 @@ acse_status validate(acse_ctx c, const acse_problem *p, const acse_options *o, b
       return fail(c, ACSE_ERR_ARG, "unknown precision");
     if (o->tile < -1 || o->tile >= gemm_num_tiles(GEMM_F64))
       return fail(c, ACSE_ERR_ARG, "tile configuration out of range");
+    if (o->flags & ~ACSE_FLAG_GENERAL_KERNELS) return fail(c, ACSE_ERR_ARG, "unknown option flags");
   }
+  c->general = o && (o->flags & ACSE_FLAG_GENERAL_KERNELS);
   return ACSE_OK;
 }
 
@@ -253,11 +257,11 @@ acse_status map_front(acse_ctx c, const acse_problem *p, GemmPrec prec, const do
       m.so1 = r3; m.so0 = 0; m.sx = r2; m.sb = 1; m.out_cols_fast = 1;
       HIP_TRY(c, launch_mode(GEMM_F64, m, OperandRef{b ? w.Hab : w.Haa, nullptr}, s));
     }
-    HIP_TRY(c, launch_g2(prec, r, Xaa, Xab, w.Haa, w.Hab, w.f, w.G2aa, w.G2ab,
+    HIP_TRY(c, launch_g2(prec, r, c->general, Xaa, Xab, w.Haa, w.Hab, w.f, w.G2aa, w.G2ab,
                          operand(w, OP_BAA, prec, r), operand(w, OP_BS, prec, r),
                          operand(w, OP_BA, prec, r), s));
     // C^T[k,l,i,j] = 4/3 sum_rs g_ir g_js G2[k,l,r,s]
-    if (r <= kSandwichMaxR) {
+    if (r <= kSandwichMaxR && !c->general) {
       HIP_TRY(c, launch_sandwich(r, w.G2aa, w.G2ab, g, 4.0 / 3.0, w.Caa, w.Cab, s));
     } else for (int b = 0; b < 2; ++b) {
       ModeArgs m1 = mode_base(r, g);  // T1[k,l,r,j] = sum_s g[j,s] G2[k,l,r,s]
@@ -271,7 +275,7 @@ acse_status map_front(acse_ctx c, const acse_problem *p, GemmPrec prec, const do
     }
     // ph A operands: L+-[(k,i),(p,s)] = sum_r g[i,r] (X_aa +- X_ab)[k,p,r,s],
     // L3[(k,j),(p,s)] = sum_r g[j,r] X_ab[k,p,s,r]
-    if (r <= kLopsMaxR) {
+    if (r <= kLopsMaxR && !c->general) {
       HIP_TRY(c, launch_lops(prec, r, ld, g, Xaa, Xab, operand(w, OP_LP, prec, r), operand(w, OP_LM, prec, r),
                              operand(w, OP_L3, prec, r), s));
       return ACSE_OK;
@@ -330,8 +334,8 @@ acse_status map_back(acse_ctx c, const acse_problem *p, double sigma, double *Oa
   const int r = p->r;
   hipStream_t s = c->stream;
   StageTimer t4(c, 4);
-  HIP_TRY(c, launch_assemble(r, p->d1, w.t, w.Zaa, w.Zab, w.Zab + (int64_t)npair_le(r) * r * r, w.Pp,
-                             w.Pm, w.E3, w.Saa, w.Sab, s));
+  HIP_TRY(c, launch_assemble(r, c->general, p->d1, w.t, w.Zaa, w.Zab,
+                             w.Zab + (int64_t)npair_le(r) * r * r, w.Pp, w.Pm, w.E3, w.Saa, w.Sab, s));
   HIP_TRY(c, launch_finish(r, sigma, w.Saa, w.Sab, w.Caa, w.Cab, Oaa, Oab, act, Maa, Mab,
                            w.partial, norm_out, s));
   return ACSE_OK;
@@ -778,8 +782,8 @@ extern "C" acse_status acse_residual_vjp(acse_ctx ctx, const acse_problem *prob,
   for (int b = 0; b < 2; ++b)
     HIP_TRY(ctx, mode(b ? w.Aab : w.Aaa, nullptr, 0.0, g, 1, r, r2, 1.0, b ? w.Hab : w.Haa, 1, r3, 0,
                       r2, 1, 1, 0));
-  HIP_TRY(ctx, launch_g2(prec, r, w.Aaa, w.Aab, w.Haa, w.Hab, w.f, w.G2aa, w.G2ab, vop(0), vop(1), vop(2),
-                         s));
+  HIP_TRY(ctx, launch_g2(prec, r, ctx->general, w.Aaa, w.Aab, w.Haa, w.Hab, w.f, w.G2aa, w.G2ab, vop(0),
+                         vop(1), vop(2), s));
   // B = A - G2, L+-, L3 and R+-, R3 are written straight into the GEMM operand
   // layouts where the products below need them.
 

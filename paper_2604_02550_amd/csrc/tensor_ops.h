@@ -79,14 +79,14 @@ constexpr int kSandwichMaxR = 64;
 hipError_t launch_sandwich(int r, const double *Xaa, const double *Xab, const double *g, double alpha,
                            double *Oaa, double *Oab, hipStream_t s);
 // G2 (natural FP64) and the packed pp B operands B_aa, B_S, B_A.
-hipError_t launch_g2(GemmPrec prec, int r, const double *Aaa, const double *Aab, const double *Haa,
-                     const double *Hab, const double *f, double *G2aa, double *G2ab,
+hipError_t launch_g2(GemmPrec prec, int r, bool general, const double *Aaa, const double *Aab,
+                     const double *Haa, const double *Hab, const double *f, double *G2aa, double *G2ab,
                      const OperandRef &Baa, const OperandRef &BS, const OperandRef &BA, hipStream_t s);
 // S from the packed pp products (Zaa [(i<j)][r^2], ZS [(i<=j)][r^2], ZA [(i<j)][r^2]),
 // the particle-hole products and the gamma-t terms.
-hipError_t launch_assemble(int r, const double *g, const double *t, const double *Zaa,
-                           const double *ZS, const double *ZA, const double *Pp, const double *Pm,
-                           const double *E3, double *Saa, double *Sab, hipStream_t s);
+hipError_t launch_assemble(int r, bool general, const double *g, const double *t,
+                           const double *Zaa, const double *ZS, const double *ZA, const double *Pp,
+                           const double *Pm, const double *E3, double *Saa, double *Sab, hipStream_t s);
 struct ActiveBits { uint64_t w[4]; };  // per-orbital active flags, r <= 256
 hipError_t launch_finish(int r, double sigma, const double *Saa, const double *Sab,
                          const double *Caa, const double *Cab, double *Oaa, double *Oab,

@@ -1582,12 +1582,12 @@ hipError_t launch_mode(GemmPrec prec, const ModeArgs &m, const OperandRef &out, 
   return hipSuccess;
 }
 
-hipError_t launch_g2(GemmPrec prec, int r, const double *Aaa, const double *Aab, const double *Haa,
-                     const double *Hab, const double *f, double *G2aa, double *G2ab,
+hipError_t launch_g2(GemmPrec prec, int r, bool general, const double *Aaa, const double *Aab,
+                     const double *Haa, const double *Hab, const double *f, double *G2aa, double *G2ab,
                      const OperandRef &Baa, const OperandRef &BS, const OperandRef &BA, hipStream_t s) {
   const size_t lds2 = (size_t)2 * r * (r + 1) * sizeof(double);
   const size_t lds3 = lds2 + (size_t)r * (r + 1) * sizeof(double);
-  const bool mir = lds3 <= kMaxLds;
+  const bool mir = !general && lds3 <= kMaxLds;
   const size_t lds = mir ? lds3 : lds2;
   const int ld_lt = (int)ld_pair_lt(r), ld_le = (int)ld_pair_le(r);
   auto go = [&](auto kern, auto tag) -> hipError_t {
@@ -1606,12 +1606,12 @@ hipError_t launch_g2(GemmPrec prec, int r, const double *Aaa, const double *Aab,
   return mir ? go(k_g2<OutBF16x3, true>, OutBF16x3{}) : go(k_g2<OutBF16x3, false>, OutBF16x3{});
 }
 
-hipError_t launch_assemble(int r, const double *g, const double *t, const double *Zaa,
-                           const double *ZS, const double *ZA, const double *Pp, const double *Pm,
-                           const double *E3, double *Saa, double *Sab, hipStream_t s) {
+hipError_t launch_assemble(int r, bool general, const double *g, const double *t,
+                           const double *Zaa, const double *ZS, const double *ZA, const double *Pp,
+                           const double *Pm, const double *E3, double *Saa, double *Sab, hipStream_t s) {
   const unsigned npairs = (unsigned)(r * (r + 1) / 2);
   const size_t slab_lds = ((size_t)3 * r * (r + 1) + 4 * (size_t)r) * sizeof(double);
-  if (slab_lds <= kMaxLds) {
+  if (!general && slab_lds <= kMaxLds) {
     hipError_t err = hipFuncSetAttribute(reinterpret_cast<const void *>(&k_assemble_slab),
                                          hipFuncAttributeMaxDynamicSharedMemorySize, (int)slab_lds);
     if (err != hipSuccess) return err;

@@ -63,3 +63,33 @@ def test_argument_errors_without_device(lib):
     lib.acse_last_error.restype = ctypes.c_char_p
     lib.acse_last_error.argtypes = [P]
     assert lib.acse_last_error(None) == b"null context"
+
+
+def test_struct_layouts_match_header(tmp_path):
+    """The binding's ctypes structs have the C header's sizes and field offsets
+    (checked with a small C program built by gcc against include/acse.h)."""
+    import shutil
+    import subprocess
+    import paper_2604_02550_amd as acse
+    gcc = shutil.which("gcc")
+    if gcc is None:
+        pytest.skip("gcc not available")
+    inc = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "include")
+    src = tmp_path / "layout.c"
+    fields = {"acse_problem": [f for f, _ in acse.Problem._fields_],
+              "acse_options": [f for f, _ in acse.Options._fields_]}
+    lines = ["#include <stdio.h>", "#include <stddef.h>", "#include \"acse.h\"", "int main(void) {"]
+    for st, fs in fields.items():
+        lines.append(f'  printf("{st} %zu\\n", sizeof({st}));')
+        for f in fs:
+            lines.append(f'  printf("{st}.{f} %zu\\n", offsetof({st}, {f}));')
+    lines += ["  return 0;", "}"]
+    src.write_text("\n".join(lines) + "\n")
+    exe = tmp_path / "layout"
+    subprocess.run([gcc, "-std=c99", "-I", inc, str(src), "-o", str(exe)], check=True)
+    out = dict(line.rsplit(" ", 1) for line in subprocess.run([str(exe)], check=True, capture_output=True,
+                                                               text=True).stdout.split("\n") if line)
+    for st, cls in (("acse_problem", acse.Problem), ("acse_options", acse.Options)):
+        assert int(out[st]) == ctypes.sizeof(cls), st
+        for f, _ in cls._fields_:
+            assert int(out[f"{st}.{f}"]) == getattr(cls, f).offset, (st, f)

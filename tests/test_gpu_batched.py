@@ -73,6 +73,13 @@ def test_small_batch_vs_oracle(ctx, tile):
         check_oracle(p, Raa, Rab, n2, TOL64)
 
 
+def test_small_batch_general_kernels(acse, ctx):
+    batch = small_batch()
+    res = ctx.residual_batched(batch, "fp64", -1, flags=acse.FLAG_GENERAL_KERNELS)
+    for p, (Raa, Rab, n2) in zip(batch, res):
+        check_oracle(p, Raa, Rab, n2, TOL64)
+
+
 def test_big_batch_equals_single_launches(ctx, big_batch):
     import torch
     res = ctx.residual_batched(big_batch, "fp64", 1)

@@ -102,6 +102,38 @@ def test_step_fp64(ctx, name, active):
     assert abs(g["norm2"] - o["norm2"]) <= TOL64 * o["norm2"]
 
 
+@pytest.mark.parametrize("name", ["tiny_fci", "r6", "r13"])
+def test_general_kernels_fp64(acse, ctx, name):
+    """The general-size transform kernels, which otherwise run only for r above the
+    limits of the faster ones (one-index transforms for the ph A operands (r > 56)
+    and for g G2 g (r > 64), G2 without mirrored-row staging and the row-chunked
+    assembly (r > 81)), selected at small r by ACSE_FLAG_GENERAL_KERNELS: residual
+    and a full step against the oracle."""
+    p = PROBLEMS[name]()
+    print(f"[general_kernels_fp64] {name} r={p['r']}", flush=True)
+    raa, rab, n2 = ost.residual(p["h"], p["V"], p["N"], p["gamma"], p["d2aa"], p["d2ab"])
+    Raa, Rab, gn2 = ctx.residual(p["h"], p["V"], p["gamma"], p["d2aa"], p["d2ab"], p["N"] // 2,
+                                 flags=acse.FLAG_GENERAL_KERNELS)
+    assert rel(cpu(Raa), raa) < TOL64 and maxrel(cpu(Raa), raa) < TOL64
+    assert rel(cpu(Rab), rab) < TOL64 and maxrel(cpu(Rab), rab) < TOL64
+    assert abs(gn2 - n2) <= TOL64 * n2
+    o = ost.step(p["h"], p["V"], p["N"], p["gamma"], p["d2aa"], p["d2ab"], 1e-3)
+    g = ctx.step(p["h"], p["V"], p["gamma"], p["d2aa"], p["d2ab"], p["N"] // 2, eps=1e-3,
+                 return_ru=True, flags=acse.FLAG_GENERAL_KERNELS)
+    for key in ("R_aa", "R_ab", "U_aa", "U_ab", "d2aa", "d2ab"):
+        assert rel(cpu(g[key]), o[key]) < TOL64, key
+        assert maxrel(cpu(g[key]), o[key]) < TOL64, key
+    assert abs(g["energy"] - o["energy"]) <= TOL64 * max(1.0, abs(o["energy"]))
+
+
+def test_unknown_option_flags_rejected(acse, ctx):
+    p = PROBLEMS["r6"]()
+    prob, keep = ctx.problem(p["h"], p["V"], p["gamma"], p["d2aa"], p["d2ab"], p["N"] // 2)
+    out = [keep[3].clone(), keep[4].clone()]
+    with pytest.raises(acse.AcseError, match="flags"):
+        ctx.residual_raw(prob, ctx.options("fp64", flags=2), out[0], out[1])
+
+
 def test_update_map_fp64(ctx):
     p = PROBLEMS["r10"]()
     o = ost.step(p["h"], p["V"], p["N"], p["gamma"], p["d2aa"], p["d2ab"], 1e-3)

@@ -86,6 +86,17 @@ def test_residual_vjp_fp64_vs_oracle(ctx, name):
         assert maxrel(got[k], ref[k]) < TOL64, (k, maxrel(got[k], ref[k]))
 
 
+def test_residual_vjp_general_kernels(acse, ctx):
+    """The adjoint with the general-size G2 kernel (ACSE_FLAG_GENERAL_KERNELS)."""
+    p = PROBLEMS["r13"]()
+    Rb = gen.cotangent(np.random.default_rng(25), p["r"])
+    ref = adj.residual_vjp(p["h"], p["V"], p["N"], p["gamma"], p["d2aa"], p["d2ab"], *Rb)
+    out = ctx.residual_vjp(p["h"], p["V"], p["gamma"], p["d2aa"], p["d2ab"], p["N"] // 2, Rb[0], Rb[1],
+                           flags=acse.FLAG_GENERAL_KERNELS)
+    for k, x in zip(KEYS, out):
+        assert rel(cpu(x), ref[k]) < TOL64, k
+
+
 @pytest.mark.parametrize("name", list(PROBLEMS))
 def test_energy_vjp_fp64_vs_oracle(ctx, name):
     p = PROBLEMS[name]()
