@@ -103,11 +103,12 @@ typedef struct {
 } acse_options;
 
 /* acse_options.flags: run the general-size transform kernels at every r (the
- * one-index transforms for the ph A operands and for the g G2 g product, the
- * G2 kernel without the mirrored-row staging and the row-chunked assembly),
- * which otherwise serve only the sizes the faster kernels do not cover
- * (r > 56, r > 64, r > 81).  Same results up to rounding order; meant for
- * verifying those kernels at small r.  Other bits are an ACSE_ERR_ARG. */
+ * one-index transforms for the ph A operands (otherwise r > 56); the G2 kernel
+ * that stores G2, followed by two one-index transforms for the g G2 g product
+ * (otherwise r > 52), without its mirrored-row staging (otherwise r > 81); the
+ * row-chunked assembly (otherwise r > 81)).  Same results up to rounding
+ * order; meant for verifying those kernels at small r.  Other bits are an
+ * ACSE_ERR_ARG. */
 #define ACSE_FLAG_GENERAL_KERNELS 1
 
 /* Creates a context on HIP device `device`, ordering work on `hip_stream`
@@ -189,7 +190,7 @@ acse_status acse_profile_enable(acse_ctx ctx, int32_t enable);
 acse_status acse_profile_read(acse_ctx ctx, acse_profile_data *out);
 
 /* Autotuner: times the grouped GEMM of one residual map per tile
- * configuration on this problem (one warm-up, then the fastest of three runs)
+ * configuration on this problem (one warm-up, then the fastest of five runs)
  * and caches the fastest configuration for (r, precision) (the size default
  * is kept unless another configuration is at least 3% faster); later calls with
  * opts->tile = -1 use it.  Writes the chosen configuration index to

@@ -38,7 +38,7 @@ namespace {
 constexpr int kNat = 26;     // natural r^4 arrays in Workspace
 constexpr int kNumOps = 12;  // GEMM operand buffers in Workspace
 constexpr int kProbsPerMap = 6;  // pair-index products of one residual map
-constexpr int kTuneReps = 3;     // timed repetitions per tile configuration in the autotuners
+constexpr int kTuneReps = 5;     // timed repetitions per tile configuration in the autotuners
 
 struct Workspace {
   // natural FP64 r^4 arrays
@@ -257,13 +257,17 @@ acse_status map_front(acse_ctx c, const acse_problem *p, GemmPrec prec, const do
       m.so1 = r3; m.so0 = 0; m.sx = r2; m.sb = 1; m.out_cols_fast = 1;
       HIP_TRY(c, launch_mode(GEMM_F64, m, OperandRef{b ? w.Hab : w.Haa, nullptr}, s));
     }
-    HIP_TRY(c, launch_g2(prec, r, c->general, Xaa, Xab, w.Haa, w.Hab, w.f, w.G2aa, w.G2ab,
-                         operand(w, OP_BAA, prec, r), operand(w, OP_BS, prec, r),
-                         operand(w, OP_BA, prec, r), s));
-    // C^T[k,l,i,j] = 4/3 sum_rs g_ir g_js G2[k,l,r,s]
-    if (r <= kSandwichMaxR && !c->general) {
-      HIP_TRY(c, launch_sandwich(r, w.G2aa, w.G2ab, g, 4.0 / 3.0, w.Caa, w.Cab, s));
-    } else for (int b = 0; b < 2; ++b) {
+    // G2, the packed pp B operands and C^T[k,l,i,j] = 4/3 sum_rs g_ir g_js G2[k,l,r,s]
+    if (r <= kG2cMaxR && !c->general) {
+      HIP_TRY(c, launch_g2c(prec, r, Xaa, Xab, w.Haa, w.Hab, w.f, g, 4.0 / 3.0, w.Caa, w.Cab,
+                            operand(w, OP_BAA, prec, r), operand(w, OP_BS, prec, r),
+                            operand(w, OP_BA, prec, r), s));
+    } else {
+      HIP_TRY(c, launch_g2(prec, r, c->general, Xaa, Xab, w.Haa, w.Hab, w.f, w.G2aa, w.G2ab,
+                           operand(w, OP_BAA, prec, r), operand(w, OP_BS, prec, r),
+                           operand(w, OP_BA, prec, r), s));
+    }
+    if (r > kG2cMaxR || c->general) for (int b = 0; b < 2; ++b) {
       ModeArgs m1 = mode_base(r, g);  // T1[k,l,r,j] = sum_s g[j,s] G2[k,l,r,s]
       m1.A = r3; m1.Bn = 1; m1.in1 = b ? w.G2ab : w.G2aa;
       m1.so1 = r; m1.so0 = 0; m1.sx = 1; m1.sb = 0; m1.out_cols_fast = 0;

@@ -73,15 +73,17 @@ hipError_t launch_mode(GemmPrec prec, const ModeArgs &m, const OperandRef &out, 
 constexpr int kLopsMaxR = 56;
 hipError_t launch_lops(GemmPrec prec, int r, int ld, const double *g, const double *Xaa, const double *Xab,
                        const OperandRef &Lp, const OperandRef &Lm, const OperandRef &L3, hipStream_t s);
-// out[k,l,:,:] = alpha g X[k,l,:,:] g for both blocks (g symmetric, r <= 64;
-// hipErrorInvalidValue above).
-constexpr int kSandwichMaxR = 64;
-hipError_t launch_sandwich(int r, const double *Xaa, const double *Xab, const double *g, double alpha,
-                           double *Oaa, double *Oab, hipStream_t s);
 // G2 (natural FP64) and the packed pp B operands B_aa, B_S, B_A.
 hipError_t launch_g2(GemmPrec prec, int r, bool general, const double *Aaa, const double *Aab,
                      const double *Haa, const double *Hab, const double *f, double *G2aa, double *G2ab,
                      const OperandRef &Baa, const OperandRef &BS, const OperandRef &BA, hipStream_t s);
+// G2 (never stored) fused with C^T[k,l,:,:] = alpha g G2[k,l,:,:] g for both
+// blocks, and the packed pp B operands; r <= kG2cMaxR (the register budget
+// of two waves per SIMD without spills).
+constexpr int kG2cMaxR = 52;
+hipError_t launch_g2c(GemmPrec prec, int r, const double *Aaa, const double *Aab, const double *Haa,
+                      const double *Hab, const double *f, const double *g, double alpha, double *Caa, double *Cab,
+                      const OperandRef &Baa, const OperandRef &BS, const OperandRef &BA, hipStream_t s);
 // S from the packed pp products (Zaa [(i<j)][r^2], ZS [(i<=j)][r^2], ZA [(i<j)][r^2]),
 // the particle-hole products and the gamma-t terms.
 hipError_t launch_assemble(int r, bool general, const double *g, const double *t,

@@ -574,116 +574,6 @@ k_lops(int r, int ld, int rp, const double *__restrict__ g, const double *__rest
 }
 
 // ---------------------------------------------------------------------------
-// Two-sided transform of r x r slices:  out[k,l,:,:] = alpha g X[k,l,:,:] g
-// (g symmetric) for the 2 r^2 slices of Xaa and Xab, i.e. C^T_kl = 4/3 g G2_kl g.
-// One pass over the data instead of two one-index transforms: per slice,
-// U = X_kl g and then g U on the FP64 MFMA, with the slice / U and g in LDS
-// (rows and columns >= r zero).  Wave w owns the 16-row output block w (NB
-// blocks per side, KS K steps of 4, both compile-time); persistent blocks walk
-// the slices with the next one prefetched into registers.
-// ---------------------------------------------------------------------------
-template <int NB, int KS>
-__global__ void __launch_bounds__(256)
-k_sandwich(int r, const double *__restrict__ Xaa, const double *__restrict__ Xab,
-           const double *__restrict__ g, double alpha, double *__restrict__ Oaa,
-           double *__restrict__ Oab) {
-  constexpr int N16 = NB * 16;
-  constexpr int LDX = N16 + 1;           // odd row stride
-  constexpr int PF = (N16 * N16) / 256;  // prefetched elements per thread (r^2 <= N16^2)
-  extern __shared__ double sw_smem[];
-  double *Xs = sw_smem;                  // [N16][LDX] slice, then U
-  double *Gs = sw_smem + N16 * LDX;      // [N16][LDX] g
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int lr = lane & 15, lk = lane >> 4;
-  const int r2 = r * r;
-  const int nsl = 2 * r2;
-  for (int e = tid; e < N16 * LDX; e += 256) {
-    const int a = e / LDX, b = e - (e / LDX) * LDX;
-    Gs[e] = (a < r && b < r) ? g[a * r + b] : 0.0;
-    Xs[e] = 0.0;
-  }
-  double v[PF];
-  auto fetch = [&](int sl) {
-    const double *src = (sl < r2 ? Xaa : Xab) + (int64_t)(sl < r2 ? sl : sl - r2) * r2;
-#pragma unroll
-    for (int q = 0; q < PF; ++q) v[q] = ld_ok(src, q * 256 + tid, q * 256 + tid < r2);
-  };
-  auto deposit = [&]() {
-#pragma unroll
-    for (int q = 0; q < PF; ++q) {
-      const int e = q * 256 + tid;
-      if (e < r2) {
-        const int a = e / r, b = e - (e / r) * r;
-        Xs[a * LDX + b] = v[q];
-      }
-    }
-  };
-  typedef double d4 __attribute__((ext_vector_type(4)));
-  int sl = blockIdx.x;
-  if (sl >= nsl) return;
-  fetch(sl);
-  __syncthreads();  // the zero fill is complete before the first deposit
-  deposit();
-  __syncthreads();
-  for (;;) {
-    const int nx = sl + (int)gridDim.x;
-    const bool more = nx < nsl;
-    if (more) fetch(nx);
-    d4 acc[NB];
-    // U[r', j] = sum_s X[r', s] g[j, s]
-#pragma unroll
-    for (int cb = 0; cb < NB; ++cb) acc[cb] = d4{0.0, 0.0, 0.0, 0.0};
-    if (wave < NB) {
-#pragma unroll
-      for (int ks = 0; ks < KS; ++ks) {
-        const int col = ks * 4 + lk;
-        const double a = Xs[(wave * 16 + lr) * LDX + col];
-#pragma unroll
-        for (int cb = 0; cb < NB; ++cb)
-          acc[cb] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, Gs[(cb * 16 + lr) * LDX + col], acc[cb], 0, 0, 0);
-      }
-    }
-    __syncthreads();  // every wave is done reading the slice
-    if (wave < NB) {
-      // accumulator item q of lane l: row lk + 4q, column lr of the block
-#pragma unroll
-      for (int cb = 0; cb < NB; ++cb)
-#pragma unroll
-        for (int q = 0; q < 4; ++q) Xs[(wave * 16 + lk + 4 * q) * LDX + cb * 16 + lr] = acc[cb][q];
-    }
-    __syncthreads();
-    // out[i, j] = alpha sum_r' g[i, r'] U[r', j]
-#pragma unroll
-    for (int cb = 0; cb < NB; ++cb) acc[cb] = d4{0.0, 0.0, 0.0, 0.0};
-    if (wave < NB) {
-#pragma unroll
-      for (int ks = 0; ks < KS; ++ks) {
-        const int kr = ks * 4 + lk;
-        const double a = Gs[(wave * 16 + lr) * LDX + kr];
-#pragma unroll
-        for (int cb = 0; cb < NB; ++cb)
-          acc[cb] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, Xs[kr * LDX + cb * 16 + lr], acc[cb], 0, 0, 0);
-      }
-      double *dst = (sl < r2 ? Oaa : Oab) + (int64_t)(sl < r2 ? sl : sl - r2) * r2;
-#pragma unroll
-      for (int cb = 0; cb < NB; ++cb) {
-        const int j = cb * 16 + lr;
-#pragma unroll
-        for (int q = 0; q < 4; ++q) {
-          const int i = wave * 16 + lk + 4 * q;
-          if (i < r && j < r) dst[i * r + j] = alpha * acc[cb][q];
-        }
-      }
-    }
-    if (!more) break;
-    __syncthreads();  // every wave is done reading U
-    deposit();
-    __syncthreads();
-    sl = nx;
-  }
-}
-
-// ---------------------------------------------------------------------------
 // G2 tensors (fold of the f and H terms) and the packed pp B operands:
 //   G2_aa[k,l,r,s] = H_aa[k,l,r,s] - H_aa[l,k,r,s]
 //                    + f[k,r] d_ls - f[k,s] d_lr - f[l,r] d_ks + f[l,s] d_kr
@@ -703,11 +593,88 @@ k_sandwich(int r, const double *__restrict__ Xaa, const double *__restrict__ Xab
 // loads would otherwise wait one latency per iteration).
 constexpr int kG2U = 4;
 
+// G2 values of element (rr, s) of row (k, l) from H_aa[k,l,rr,s] (hn),
+// H_aa[l,k,rr,s] (hm), H_ab[k,l,rr,s] (bn), H_ab[l,k,s,rr] (bt) and the rows
+// fk = f[k,:], fl = f[l,:].
+__device__ inline void g2_element(int k, int l, int rr, int s, double hn, double hm, double bn, double bt,
+                                  const double *fk, const double *fl, double &gaa, double &gab) {
+  gaa = hn - hm;
+  if (l == s) gaa += fk[rr];
+  if (l == rr) gaa -= fk[s];
+  if (k == s) gaa -= fl[rr];
+  if (k == rr) gaa += fl[s];
+  gab = bn + bt;
+  if (l == s) gab += fk[rr];
+  if (k == rr) gab += fl[s];
+}
+
+// Pair tables in LDS: tle[q] = (a << 8) | b for the pairs a <= b in packed
+// order, tlt[q] likewise for a < b (r <= 256), so the packing loops do not
+// solve for (a, b) per element.
+__device__ inline void pair_tables(int r, uint16_t *tle, uint16_t *tlt, int tid, int nt) {
+  const int nle = npair_le(r), nlt = npair_lt(r);
+  for (int q = tid; q < nle; q += nt) {
+    int a, b;
+    unpair_le(r, q, a, b);
+    tle[q] = (uint16_t)((a << 8) | b);
+  }
+  for (int q = tid; q < nlt; q += nt) {
+    int a, b;
+    unpair_lt(r, q, a, b);
+    tlt[q] = (uint16_t)((a << 8) | b);
+  }
+}
+
+// Packed pp B operand row `row` (K padding included) from the natural rows
+// B_aa = ba, B_ab = bb held in LDS with row stride rp; pair tables from
+// pair_tables, or null to solve for each pair.
+template <class O>
+__device__ inline void g2_pack(int r, int64_t row, int ld_lt, int ld_le, const double *ba, const double *bb,
+                               int rp, const uint16_t *tle, const uint16_t *tlt, const O &Baa, const O &BS,
+                               const O &BA, int tid, int nt) {
+  const int nle = npair_le(r), nlt = npair_lt(r);
+  for (int q = tid; q < ld_le; q += nt) {
+    double v = 0.0;
+    if (q < nle) {
+      int a, b;
+      if (tle) {
+        a = tle[q] >> 8;
+        b = tle[q] & 255;
+      } else {
+        unpair_le(r, q, a, b);
+      }
+      v = bb[a * rp + b] + bb[b * rp + a];
+    }
+    BS.put(row * ld_le + q, v);
+  }
+  for (int q = tid; q < ld_lt; q += nt) {
+    double va = 0.0, vb = 0.0;
+    if (q < nlt) {
+      int a, b;
+      if (tlt) {
+        a = tlt[q] >> 8;
+        b = tlt[q] & 255;
+      } else {
+        unpair_lt(r, q, a, b);
+      }
+      va = ba[a * rp + b] - ba[b * rp + a];
+      vb = bb[a * rp + b] - bb[b * rp + a];
+    }
+    Baa.put(row * ld_lt + q, va);
+    BA.put(row * ld_lt + q, vb);
+  }
+}
+
+// LDS bytes of the two pair tables of r (rounded to 16)
+__host__ __device__ inline size_t pair_table_bytes(int r) {
+  return ((size_t)(r * (r + 1) / 2 + r * (r - 1) / 2) * sizeof(uint16_t) + 15) / 16 * 16;
+}
+
 template <class O, bool MIR>
 __global__ void __launch_bounds__(512)
 k_g2(int r, int ld_lt, int ld_le, const double *__restrict__ Aaa, const double *__restrict__ Aab,
      const double *__restrict__ Haa, const double *__restrict__ Hab, const double *__restrict__ f,
-     double *__restrict__ G2aa, double *__restrict__ G2ab, O Baa, O BS, O BA) {
+     double *__restrict__ G2aa, double *__restrict__ G2ab, O Baa, O BS, O BA, int use_tables) {
   extern __shared__ double g2_smem[];
   constexpr int NT = 512, U = kG2U;
   const int r2 = r * r, RP = r + 1;
@@ -715,7 +682,13 @@ k_g2(int r, int ld_lt, int ld_le, const double *__restrict__ Aaa, const double *
   const int k = row / r, l = row - (row / r) * r;
   const int64_t nat0 = (int64_t)row * r2, mir0 = ((int64_t)l * r + k) * r2;
   double *ba = g2_smem, *bb = g2_smem + r * RP, *mh = g2_smem + 2 * r * RP;
+  uint16_t *tle = nullptr, *tlt = nullptr;
   const int tid = threadIdx.x;
+  if (use_tables) {
+    tle = reinterpret_cast<uint16_t *>(g2_smem + (MIR ? 3 : 2) * r * RP);
+    tlt = tle + npair_le(r);
+    pair_tables(r, tle, tlt, tid, NT);
+  }
   if constexpr (MIR) {
     for (int base = 0; base < r2; base += NT * U) {
       double v[U];
@@ -755,14 +728,9 @@ k_g2(int r, int ld_lt, int ld_le, const double *__restrict__ Aaa, const double *
       const int e = base + u * NT + tid;
       if (e >= r2) continue;
       const int rr = e / r, s = e - (e / r) * r;
-      double gaa = hn[u] - hm[u];
-      if (l == s) gaa += f[k * r + rr];
-      if (l == rr) gaa -= f[k * r + s];
-      if (k == s) gaa -= f[l * r + rr];
-      if (k == rr) gaa += f[l * r + s];
-      double gab = bn[u] + (MIR ? mh[s * RP + rr] : bm[u]);
-      if (l == s) gab += f[k * r + rr];
-      if (k == rr) gab += f[l * r + s];
+      double gaa, gab;
+      g2_element(k, l, rr, s, hn[u], hm[u], bn[u], MIR ? mh[s * RP + rr] : bm[u], f + k * r, f + l * r, gaa,
+                 gab);
       G2aa[nat0 + e] = gaa;
       G2ab[nat0 + e] = gab;
       ba[rr * RP + s] = an[u] - gaa;
@@ -770,26 +738,149 @@ k_g2(int r, int ld_lt, int ld_le, const double *__restrict__ Aaa, const double *
     }
   }
   __syncthreads();
-  const int nle = npair_le(r), nlt = npair_lt(r);
-  for (int q = tid; q < ld_le; q += NT) {
-    double v = 0.0;
-    if (q < nle) {
-      int a, b;
-      unpair_le(r, q, a, b);
-      v = bb[a * RP + b] + bb[b * RP + a];
-    }
-    BS.put((int64_t)row * ld_le + q, v);
+  g2_pack(r, row, ld_lt, ld_le, ba, bb, RP, tle, tlt, Baa, BS, BA, tid, NT);
+}
+
+// ---------------------------------------------------------------------------
+// G2 fused with C^T = alpha g G2 g (r <= 52): the G2 rows never leave LDS.
+// Persistent blocks of 8 waves walk the rows (k,l).  Per row: the mirrored
+// H_ab row is staged; G2_aa, G2_ab (zero-padded r x r matrices, row stride
+// 4 KS + 2) and B = A - G2 go to LDS; the packed pp B operands are written;
+// then waves 0-3 (alpha-alpha) and 4-7 (alpha-beta) form U^T = g G2^T and
+// C = alpha g U on the FP64 MFMA, with g (symmetric) as the A operand held in
+// registers (wave w: rows 16 (w mod 4)..) and the B operands read transposed
+// from LDS (conflict-free for a row stride = 2 mod 4).  The next row's inputs
+// are loaded into registers while the MFMAs run.
+// ---------------------------------------------------------------------------
+template <class O, int KS>
+__global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(2)))
+k_g2c(int r, int ld_lt, int ld_le, const double *__restrict__ Aaa, const double *__restrict__ Aab,
+      const double *__restrict__ Haa, const double *__restrict__ Hab, const double *__restrict__ f,
+      const double *__restrict__ g, double alpha, double *__restrict__ Caa, double *__restrict__ Cab,
+      O Baa, O BS, O BA, int nrow) {
+  constexpr int NT = 512;
+  constexpr int NB = (4 * KS + 15) / 16, NR = 16 * NB, RP = 4 * KS + 2;
+  constexpr int PF = (4 * KS * 4 * KS + NT - 1) / NT;  // elements of one row per thread (r <= 4 KS)
+  extern __shared__ double g2c_smem[];
+  double *const G = g2c_smem;                 // [2][NR][RP]: G2_aa, G2_ab
+  double *const Z = g2c_smem + 2 * NR * RP;   // B_aa, B_ab, mirrored H_ab ([r][RP] each), later [2][NR][RP] U^T
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int lr = lane & 15, lk = lane >> 4;
+  const int blk = wave & 3, side = wave >> 2;
+  const int r2 = r * r;
+  double *const Ba = Z, *const Bb = Z + r * RP, *const MH = Z + 2 * r * RP;
+  // rows k and l of f for the current row, then the pair tables (after the Z region)
+  double *const FK = Z + (3 * r * RP > 2 * NR * RP ? 3 * r * RP : 2 * NR * RP), *const FL = FK + r;
+  uint16_t *const tle = reinterpret_cast<uint16_t *>(FL + r), *const tlt = tle + npair_le(r);
+  pair_tables(r, tle, tlt, tid, NT);
+  double afr[KS];
+#pragma unroll
+  for (int ks = 0; ks < KS; ++ks) {
+    const int x = blk * 16 + lr, y = ks * 4 + lk;
+    const bool ok = x < r && y < r;
+    const double v = ld_ok(g, (int64_t)x * r + y, ok);
+    afr[ks] = ok ? v : 0.0;
   }
-  for (int q = tid; q < ld_lt; q += NT) {
-    double va = 0.0, vb = 0.0;
-    if (q < nlt) {
-      int a, b;
-      unpair_lt(r, q, a, b);
-      va = ba[a * RP + b] - ba[b * RP + a];
-      vb = bb[a * RP + b] - bb[b * RP + a];
+  for (int e = tid; e < 2 * NR * RP; e += NT) G[e] = 0.0;
+  double vhn[PF], vhm[PF], vbn[PF], vbm[PF], van[PF], vab[PF];
+  auto fetch = [&](int rw) {
+    const int kk = rw / r, ll = rw - (rw / r) * r;
+    const int64_t nat0 = (int64_t)rw * r2, mir0 = ((int64_t)ll * r + kk) * r2;
+#pragma unroll
+    for (int u = 0; u < PF; ++u) {
+      const int e = tid + u * NT;
+      const bool ok = e < r2;
+      vhn[u] = ld_ok(Haa, nat0 + e, ok);
+      vhm[u] = ld_ok(Haa, mir0 + e, ok);
+      vbn[u] = ld_ok(Hab, nat0 + e, ok);
+      vbm[u] = ld_ok(Hab, mir0 + e, ok);
+      van[u] = ld_ok(Aaa, nat0 + e, ok);
+      vab[u] = ld_ok(Aab, nat0 + e, ok);
     }
-    Baa.put((int64_t)row * ld_lt + q, va);
-    BA.put((int64_t)row * ld_lt + q, vb);
+  };
+  int row = blockIdx.x;
+  fetch(row);
+  __syncthreads();  // zero fill of G complete
+  for (;;) {
+    const int k = row / r, l = row - (row / r) * r;
+#pragma unroll
+    for (int u = 0; u < PF; ++u) {
+      const int e = tid + u * NT;
+      if (e < r2) {
+        const int x = e / r, y = e - (e / r) * r;
+        MH[x * RP + y] = vbm[u];
+      }
+    }
+    if (tid < r) FK[tid] = f[k * r + tid];
+    else if (tid - 256 >= 0 && tid - 256 < r) FL[tid - 256] = f[l * r + tid - 256];
+    __syncthreads();
+#pragma unroll
+    for (int u = 0; u < PF; ++u) {
+      const int e = tid + u * NT;
+      if (e < r2) {
+        const int rr = e / r, s = e - (e / r) * r;
+        double gaa, gab;
+        g2_element(k, l, rr, s, vhn[u], vhm[u], vbn[u], MH[s * RP + rr], FK, FL, gaa, gab);
+        G[rr * RP + s] = gaa;
+        G[NR * RP + rr * RP + s] = gab;
+        Ba[rr * RP + s] = van[u] - gaa;
+        Bb[rr * RP + s] = vab[u] - gab;
+      }
+    }
+    __syncthreads();
+    g2_pack(r, (int64_t)row, ld_lt, ld_le, Ba, Bb, RP, tle, tlt, Baa, BS, BA, tid, NT);
+    const int next = row + (int)gridDim.x;
+    const bool more = next < nrow;
+    __syncthreads();  // B and the mirrored row are read; U^T may overwrite them
+    if (more) fetch(next);
+    const double *Gs = G + side * NR * RP;
+    double *Us = Z + side * NR * RP;
+    mode_d4 acc[NB];
+    if (blk < NB) {
+      // U^T[j][r'] = sum_s g[j][s] G2[r'][s]; accumulator item v of lane l:
+      // row j = 16 blk + l/16 + 4v, column r' = 16 cb + l%16
+#pragma unroll
+      for (int cb = 0; cb < NB; ++cb) acc[cb] = mode_d4{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+      for (int ks = 0; ks < KS; ++ks) {
+        const int kr = ks * 4 + lk;
+#pragma unroll
+        for (int cb = 0; cb < NB; ++cb)
+          acc[cb] = __builtin_amdgcn_mfma_f64_16x16x4f64(afr[ks], Gs[(cb * 16 + lr) * RP + kr], acc[cb], 0, 0, 0);
+      }
+#pragma unroll
+      for (int cb = 0; cb < NB; ++cb)
+        if (cb * 16 + lr < 4 * KS) {
+#pragma unroll
+          for (int v = 0; v < 4; ++v) Us[(blk * 16 + lk + 4 * v) * RP + cb * 16 + lr] = acc[cb][v];
+        }
+    }
+    __syncthreads();
+    if (blk < NB) {
+      // C[i][j] = alpha sum_r' g[i][r'] U^T[j][r']
+#pragma unroll
+      for (int cb = 0; cb < NB; ++cb) acc[cb] = mode_d4{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+      for (int ks = 0; ks < KS; ++ks) {
+        const int kr = ks * 4 + lk;
+#pragma unroll
+        for (int cb = 0; cb < NB; ++cb)
+          acc[cb] = __builtin_amdgcn_mfma_f64_16x16x4f64(afr[ks], Us[(cb * 16 + lr) * RP + kr], acc[cb], 0, 0, 0);
+      }
+      double *dst = (side ? Cab : Caa) + (int64_t)row * r2;
+#pragma unroll
+      for (int cb = 0; cb < NB; ++cb) {
+        const int j = cb * 16 + lr;
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int i = blk * 16 + lk + 4 * v;
+          if (i < r && j < r) dst[i * r + j] = alpha * acc[cb][v];
+        }
+      }
+    }
+    if (!more) break;
+    __syncthreads();  // G and U^T are read before the next row overwrites them
+    row = next;
   }
 }
 
@@ -1539,39 +1630,6 @@ static hipError_t launch_mode_o(const ModeArgs &m, O out, hipStream_t s) {
   return m.in2 ? launch_mode_h<O, true>(m, out, s) : launch_mode_h<O, false>(m, out, s);
 }
 
-template <int NB, int KS>
-static hipError_t launch_sandwich_t(int r, const double *Xaa, const double *Xab, const double *g,
-                                    double alpha, double *Oaa, double *Oab, hipStream_t s) {
-  static int resident = 0;  // blocks the device holds at once
-  const size_t lds = (size_t)2 * (NB * 16) * (NB * 16 + 1) * sizeof(double);
-  const void *fn = reinterpret_cast<const void *>(&k_sandwich<NB, KS>);
-  if (resident == 0) {
-    int dev = 0, cus = 0, per_cu = 0;
-    hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-    if (e == hipSuccess) e = hipGetDevice(&dev);
-    if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
-    if (e == hipSuccess) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, 256, lds);
-    if (e != hipSuccess) return e;
-    resident = cus * std::max(per_cu, 1);
-  }
-  const int nsl = 2 * r * r;
-  hipLaunchKernelGGL((k_sandwich<NB, KS>), dim3(std::min(nsl, resident)), dim3(256), lds, s, r, Xaa, Xab,
-                     g, alpha, Oaa, Oab);
-  return hipGetLastError();
-}
-
-hipError_t launch_sandwich(int r, const double *Xaa, const double *Xab, const double *g, double alpha,
-                           double *Oaa, double *Oab, hipStream_t s) {
-  switch ((r + 3) / 4) {
-#define ACSE_SW(K) \
-    case K: return launch_sandwich_t<(4 * K + 15) / 16, K>(r, Xaa, Xab, g, alpha, Oaa, Oab, s);
-    ACSE_SW(1) ACSE_SW(2) ACSE_SW(3) ACSE_SW(4) ACSE_SW(5) ACSE_SW(6) ACSE_SW(7) ACSE_SW(8)
-    ACSE_SW(9) ACSE_SW(10) ACSE_SW(11) ACSE_SW(12) ACSE_SW(13) ACSE_SW(14) ACSE_SW(15) ACSE_SW(16)
-#undef ACSE_SW
-    default: return hipErrorInvalidValue;  // r > 64: the caller uses two one-index transforms
-  }
-}
-
 hipError_t launch_mode(GemmPrec prec, const ModeArgs &m, const OperandRef &out, hipStream_t s) {
   if (m.r < 2 || m.r > kModeMaxR) return hipErrorInvalidValue;
   if (m.accumulate) {
@@ -1588,7 +1646,8 @@ hipError_t launch_g2(GemmPrec prec, int r, bool general, const double *Aaa, cons
   const size_t lds2 = (size_t)2 * r * (r + 1) * sizeof(double);
   const size_t lds3 = lds2 + (size_t)r * (r + 1) * sizeof(double);
   const bool mir = !general && lds3 <= kMaxLds;
-  const size_t lds = mir ? lds3 : lds2;
+  const int tables = (mir ? lds3 : lds2) + pair_table_bytes(r) <= kMaxLds;
+  const size_t lds = (mir ? lds3 : lds2) + (tables ? pair_table_bytes(r) : 0);
   const int ld_lt = (int)ld_pair_lt(r), ld_le = (int)ld_pair_le(r);
   auto go = [&](auto kern, auto tag) -> hipError_t {
     using O = decltype(tag);
@@ -1596,7 +1655,7 @@ hipError_t launch_g2(GemmPrec prec, int r, bool general, const double *Aaa, cons
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(kern, dim3((unsigned)(r * r)), dim3(512), lds, s, r, ld_lt, ld_le, Aaa, Aab, Haa,
-                       Hab, f, G2aa, G2ab, make_out<O>(Baa), make_out<O>(BS), make_out<O>(BA));
+                       Hab, f, G2aa, G2ab, make_out<O>(Baa), make_out<O>(BS), make_out<O>(BA), tables);
     return hipGetLastError();
   };
   if (prec == GEMM_F64)
@@ -1604,6 +1663,55 @@ hipError_t launch_g2(GemmPrec prec, int r, bool general, const double *Aaa, cons
   if (prec == GEMM_F32)
     return mir ? go(k_g2<OutF32, true>, OutF32{}) : go(k_g2<OutF32, false>, OutF32{});
   return mir ? go(k_g2<OutBF16x3, true>, OutBF16x3{}) : go(k_g2<OutBF16x3, false>, OutBF16x3{});
+}
+
+template <class O, int KS>
+static hipError_t launch_g2c_t(int r, const double *Aaa, const double *Aab, const double *Haa, const double *Hab,
+                               const double *f, const double *g, double alpha, double *Caa, double *Cab, O Baa,
+                               O BS, O BA, hipStream_t s) {
+  static int resident = 0;  // blocks the device holds at once
+  constexpr int NR = 16 * ((4 * KS + 15) / 16), RP = 4 * KS + 2;
+  const size_t lds =
+      ((size_t)2 * NR * RP + std::max((size_t)3 * r * RP, (size_t)2 * NR * RP) + 2 * (size_t)r) * sizeof(double) +
+      pair_table_bytes(r);
+  const void *fn = reinterpret_cast<const void *>(&k_g2c<O, KS>);
+  hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  if (e != hipSuccess) return e;
+  if (resident == 0) {
+    int dev = 0, cus = 0, per_cu = 0;
+    e = hipGetDevice(&dev);
+    if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    if (e == hipSuccess) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, 512, lds);
+    if (e != hipSuccess) return e;
+    resident = cus * std::max(per_cu, 1);
+  }
+  const int nrow = r * r;
+  hipLaunchKernelGGL((k_g2c<O, KS>), dim3(std::min(nrow, resident)), dim3(512), lds, s, r, (int)ld_pair_lt(r),
+                     (int)ld_pair_le(r), Aaa, Aab, Haa, Hab, f, g, alpha, Caa, Cab, Baa, BS, BA, nrow);
+  return hipGetLastError();
+}
+
+template <class O>
+static hipError_t launch_g2c_o(int r, const double *Aaa, const double *Aab, const double *Haa, const double *Hab,
+                               const double *f, const double *g, double alpha, double *Caa, double *Cab, O Baa,
+                               O BS, O BA, hipStream_t s) {
+  switch ((r + 3) / 4) {
+#define ACSE_G2C(K) \
+    case K: return launch_g2c_t<O, K>(r, Aaa, Aab, Haa, Hab, f, g, alpha, Caa, Cab, Baa, BS, BA, s);
+    ACSE_G2C(1) ACSE_G2C(2) ACSE_G2C(3) ACSE_G2C(4) ACSE_G2C(5) ACSE_G2C(6) ACSE_G2C(7) ACSE_G2C(8)
+    ACSE_G2C(9) ACSE_G2C(10) ACSE_G2C(11) ACSE_G2C(12) ACSE_G2C(13)
+#undef ACSE_G2C
+    default: return hipErrorInvalidValue;
+  }
+}
+
+hipError_t launch_g2c(GemmPrec prec, int r, const double *Aaa, const double *Aab, const double *Haa,
+                      const double *Hab, const double *f, const double *g, double alpha, double *Caa, double *Cab,
+                      const OperandRef &Baa, const OperandRef &BS, const OperandRef &BA, hipStream_t s) {
+  if (r < 2 || r > kG2cMaxR) return hipErrorInvalidValue;
+  ACSE_DISPATCH_OUT(prec, return launch_g2c_o(r, Aaa, Aab, Haa, Hab, f, g, alpha, Caa, Cab, make_out<O>(Baa),
+                                              make_out<O>(BS), make_out<O>(BA), s));
+  return hipSuccess;
 }
 
 hipError_t launch_assemble(int r, bool general, const double *g, const double *t,

@@ -105,10 +105,11 @@ def test_step_fp64(ctx, name, active):
 @pytest.mark.parametrize("name", ["tiny_fci", "r6", "r13"])
 def test_general_kernels_fp64(acse, ctx, name):
     """The general-size transform kernels, which otherwise run only for r above the
-    limits of the faster ones (one-index transforms for the ph A operands (r > 56)
-    and for g G2 g (r > 64), G2 without mirrored-row staging and the row-chunked
-    assembly (r > 81)), selected at small r by ACSE_FLAG_GENERAL_KERNELS: residual
-    and a full step against the oracle."""
+    limits of the faster ones (one-index transforms for the ph A operands (r > 56);
+    the G2 kernel that stores G2 plus two one-index transforms for g G2 g (r > 52),
+    without mirrored-row staging (r > 81); the row-chunked assembly (r > 81)),
+    selected at small r by ACSE_FLAG_GENERAL_KERNELS: residual and a full step
+    against the oracle."""
     p = PROBLEMS[name]()
     print(f"[general_kernels_fp64] {name} r={p['r']}", flush=True)
     raa, rab, n2 = ost.residual(p["h"], p["V"], p["N"], p["gamma"], p["d2aa"], p["d2ab"])
