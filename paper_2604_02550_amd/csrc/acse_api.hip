@@ -247,7 +247,17 @@ acse_status map_front(acse_ctx c, const acse_problem *p, GemmPrec prec, const do
   hipStream_t s = c->stream;
   {
     StageTimer t2(c, 2);
-    HIP_TRY(c, launch_f(r, Xaa, Xab, g, w.fpart, w.f, s));
+    // ph A operands: L+-[(k,i),(p,s)] = sum_r g[i,r] (X_aa +- X_ab)[k,p,r,s],
+    // L3[(k,j),(p,s)] = sum_r g[j,r] X_ab[k,p,s,r]; the one-pass kernel also
+    // leaves the partials of f
+    const bool lops = r <= kLopsMaxR && !c->general;
+    if (lops) {
+      HIP_TRY(c, launch_lops(prec, r, ld, g, Xaa, Xab, operand(w, OP_LP, prec, r), operand(w, OP_LM, prec, r),
+                             operand(w, OP_L3, prec, r), w.fpart, s));
+      HIP_TRY(c, launch_f_reduce(r, w.fpart, w.f, s));
+    } else {
+      HIP_TRY(c, launch_f(r, Xaa, Xab, g, w.fpart, w.f, s));
+    }
     HIP_TRY(c, launch_t(r, w.Waa, Xaa, w.Wab, Xab, w.tpart, w.t, s));
 
     // H[k,l,(r,s)] = sum_p X[k,p,(r,s)] g[p,l]
@@ -277,13 +287,8 @@ acse_status map_front(acse_ctx c, const acse_problem *p, GemmPrec prec, const do
       m2.so1 = r2; m2.so0 = 0; m2.sx = r; m2.sb = 1; m2.out_cols_fast = 1;
       HIP_TRY(c, launch_mode(GEMM_F64, m2, OperandRef{b ? w.Cab : w.Caa, nullptr}, s));
     }
-    // ph A operands: L+-[(k,i),(p,s)] = sum_r g[i,r] (X_aa +- X_ab)[k,p,r,s],
-    // L3[(k,j),(p,s)] = sum_r g[j,r] X_ab[k,p,s,r]
-    if (r <= kLopsMaxR && !c->general) {
-      HIP_TRY(c, launch_lops(prec, r, ld, g, Xaa, Xab, operand(w, OP_LP, prec, r), operand(w, OP_LM, prec, r),
-                             operand(w, OP_L3, prec, r), s));
-      return ACSE_OK;
-    }
+    if (lops) return ACSE_OK;
+    // ph A operands by three one-index transforms
     for (int q : {OP_LP, OP_LM, OP_L3})
       HIP_TRY(c, launch_zero_kpad(prec, r, ld, operand(w, q, prec, r), s));
     for (int b = 0; b < 2; ++b) {

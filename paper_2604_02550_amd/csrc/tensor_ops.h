@@ -68,11 +68,15 @@ hipError_t launch_f(int r, const double *Aaa, const double *Aab, const double *g
                     double *f, hipStream_t s);
 hipError_t launch_mode(GemmPrec prec, const ModeArgs &m, const OperandRef &out, hipStream_t s);
 // ph A operands L+, L-, L3 (rows (k,i), K (p,s), leading dimension ld, K
-// padding zeroed) in one pass over X_aa, X_ab; r <= kLopsMaxR (the register
+// padding zeroed) in one pass over X_aa, X_ab, and optionally the partials
+// [k][p][s] of f (as launch_f's first kernel); r <= kLopsMaxR (the register
 // budget of two waves per SIMD; larger r use three one-index transforms).
 constexpr int kLopsMaxR = 56;
 hipError_t launch_lops(GemmPrec prec, int r, int ld, const double *g, const double *Xaa, const double *Xab,
-                       const OperandRef &Lp, const OperandRef &Lm, const OperandRef &L3, hipStream_t s);
+                       const OperandRef &Lp, const OperandRef &Lm, const OperandRef &L3, double *fpart,
+                       hipStream_t s);
+// f[k,s] = sum_p part[k,p,s] (the second half of launch_f, for partials from launch_lops).
+hipError_t launch_f_reduce(int r, const double *part, double *f, hipStream_t s);
 // G2 (natural FP64) and the packed pp B operands B_aa, B_S, B_A.
 hipError_t launch_g2(GemmPrec prec, int r, bool general, const double *Aaa, const double *Aab,
                      const double *Haa, const double *Hab, const double *f, double *G2aa, double *G2ab,

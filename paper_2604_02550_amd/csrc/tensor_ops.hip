@@ -451,7 +451,9 @@ k_mode(ModeArgs m, O out, int npanels) {
 // during the MFMAs), g is the FP64 MFMA A operand held in registers (wave w:
 // output rows 16w..16w+15), and the output rows (k,i) get the 16-column runs
 // (p, s).  The block that handles p = r - 1 also zeroes the K padding of the
-// r rows (k, .) of all three operands.  LDS row stride: >= 4 KS and = 2 mod 4,
+// r rows (k, .) of all three operands.  With fpart set, the slab's partial of
+// f[k,s] = sum_pr (X_aa[k,p,r,s] - X_ab[k,p,s,r]) g[p,r] (the sum over r, in
+// the order of k_f_partial) is written too, [k][p][s].  LDS row stride: >= 4 KS and = 2 mod 4,
 // which keeps the transposed reads of X_ab conflict-free.
 // ---------------------------------------------------------------------------
 static inline int lops_rp(int ks) { return 4 * ks + 2; }
@@ -459,7 +461,7 @@ static inline int lops_rp(int ks) { return 4 * ks + 2; }
 template <class O, int KS>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2)))
 k_lops(int r, int ld, int rp, const double *__restrict__ g, const double *__restrict__ Xaa,
-       const double *__restrict__ Xab, O Lp, O Lm, O L3, int nslab) {
+       const double *__restrict__ Xab, O Lp, O Lm, O L3, int nslab, double *__restrict__ fpart) {
   constexpr int CB = (4 * KS + 15) / 16;   // 16-column output blocks (and 16-row blocks)
   constexpr int NR = CB * 16;              // staged rows (>= 4 KS, >= r)
   constexpr int PF = (4 * KS * 4 * KS + 255) / 256;  // prefetched elements per thread per slab
@@ -508,6 +510,12 @@ k_lops(int r, int ld, int rp, const double *__restrict__ g, const double *__rest
     const bool more = qn < nslab;
     if (more) fetch(qn);
     const int k = q / r, p = q - (q / r) * r;
+    if (fpart && tid < r) {
+      // f partial of the slab: sum_r (X_aa[k,p,r,s] - X_ab[k,p,s,r]) g[p,r], s = tid
+      double a = 0.0;
+      for (int rr = 0; rr < r; ++rr) a += (SA[rr * rp + tid] - SB[tid * rp + rr]) * g[p * r + rr];
+      fpart[(int64_t)q * r + tid] = a;  // [k][p][s]
+    }
     // accumulator item v of lane l: output row 16 wave + l/16 + 4v, column 16 cb + l%16
     auto store = [&](const mode_d4 *acc, O &out) {
 #pragma unroll
@@ -1188,7 +1196,7 @@ constexpr int kTLdx = kTChunk + 1;  // odd LDS row stride
 
 // NB = ceil(r / 16) output blocks per side (compile time, so the MFMA chains
 // are straight-line code); wave w owns block rows w and w + 4.
-template <int NB>
+template <int NB, bool TWO>
 __global__ void __launch_bounds__(256)
 k_t_partial(int r, const double *__restrict__ P1, const double *__restrict__ Q1,
             const double *__restrict__ P2, const double *__restrict__ Q2, double w1, double w2,
@@ -1208,35 +1216,47 @@ k_t_partial(int r, const double *__restrict__ P1, const double *__restrict__ Q1,
   for (int a = 0; a < NBW; ++a)
 #pragma unroll
     for (int b = 0; b < NB; ++b) acc[a][b] = d4{0.0, 0.0, 0.0, 0.0};
-  const bool two = P2 != nullptr;
-  for (int64_t xc = x0; xc < x1; xc += kTChunk) {
-    // stage rows [0, rows) x columns [xc, xc + kTChunk): 4 arrays
-    for (int e0 = 0; e0 < rows * kTChunk; e0 += 256 * kStage) {
-      double v[kStage][4];
+  // The chunk's elements go through registers: the loads of chunk c + 1 are
+  // in flight while the MFMAs of chunk c run.
+  constexpr int PER = rows * kTChunk / 256;  // elements per thread per array
+  static_assert(PER * 256 == rows * kTChunk, "chunk must split evenly over the block");
+  double v[PER][4];
+  auto fetch = [&](int64_t xc) {
 #pragma unroll
-      for (int u = 0; u < kStage; ++u) {
-        const int e = e0 + u * 256 + tid;
-        const int j = e / kTChunk, c = e - (e / kTChunk) * kTChunk;
-        const bool ok = e < rows * kTChunk && j < r && xc + c < x1;
-        const int64_t o = (int64_t)j * X + xc + c;
-        v[u][0] = ld_ok(P1, o, ok);
-        v[u][1] = ld_ok(Q1, o, ok);
-        v[u][2] = two ? ld_ok(P2, o, ok) : 0.0;
-        v[u][3] = two ? ld_ok(Q2, o, ok) : 0.0;
-        if (!ok) v[u][0] = v[u][1] = v[u][2] = v[u][3] = 0.0;
-      }
-#pragma unroll
-      for (int u = 0; u < kStage; ++u) {
-        const int e = e0 + u * 256 + tid;
-        if (e >= rows * kTChunk) break;
-        const int j = e / kTChunk, c = e - (e / kTChunk) * kTChunk;
-        sP1[j * kTLdx + c] = w1 * v[u][0];
-        sQ1[j * kTLdx + c] = v[u][1];
-        sP2[j * kTLdx + c] = w2 * v[u][2];
-        sQ2[j * kTLdx + c] = v[u][3];
+    for (int u = 0; u < PER; ++u) {
+      const int e = u * 256 + tid;
+      const int j = e / kTChunk, c = e - (e / kTChunk) * kTChunk;
+      const bool ok = j < r && xc + c < x1;
+      const int64_t o = (int64_t)j * X + xc + c;
+      v[u][0] = ld_ok(P1, o, ok);
+      v[u][1] = ld_ok(Q1, o, ok);
+      if constexpr (TWO) {
+        v[u][2] = ld_ok(P2, o, ok);
+        v[u][3] = ld_ok(Q2, o, ok);
       }
     }
+  };
+  // (out-of-range elements are zeroed here, not in fetch, so that nothing
+  // waits for the loads before the MFMAs)
+  auto deposit = [&](int64_t xc) {
+#pragma unroll
+    for (int u = 0; u < PER; ++u) {
+      const int e = u * 256 + tid;
+      const int j = e / kTChunk, c = e - (e / kTChunk) * kTChunk;
+      const bool ok = j < r && xc + c < x1;
+      sP1[j * kTLdx + c] = ok ? w1 * v[u][0] : 0.0;
+      sQ1[j * kTLdx + c] = ok ? v[u][1] : 0.0;
+      if constexpr (TWO) {
+        sP2[j * kTLdx + c] = ok ? w2 * v[u][2] : 0.0;
+        sQ2[j * kTLdx + c] = ok ? v[u][3] : 0.0;
+      }
+    }
+  };
+  if (x0 < x1) fetch(x0);
+  for (int64_t xc = x0; xc < x1; xc += kTChunk) {
+    deposit(xc);
     __syncthreads();
+    if (xc + kTChunk < x1) fetch(xc + kTChunk);
     if (wave < NB) {
 #pragma unroll
       for (int st = 0; st < kTChunk / 4; ++st) {
@@ -1245,23 +1265,26 @@ k_t_partial(int r, const double *__restrict__ P1, const double *__restrict__ Q1,
 #pragma unroll
         for (int kb = 0; kb < NB; ++kb) {
           b1[kb] = sQ1[(kb * 16 + lr) * kTLdx + col];
-          b2[kb] = sQ2[(kb * 16 + lr) * kTLdx + col];
+          if constexpr (TWO) b2[kb] = sQ2[(kb * 16 + lr) * kTLdx + col];
         }
 #pragma unroll
         for (int a = 0; a < NBW; ++a) {
           // NBW = 2 only for NB > 4: the second row block of wave w is w + 4 (< NB when w < NB - 4)
           const int jb = wave + 4 * a < NB ? wave + 4 * a : wave;
           const double a1 = sP1[(jb * 16 + lr) * kTLdx + col];
-          const double a2 = sP2[(jb * 16 + lr) * kTLdx + col];
 #pragma unroll
-          for (int kb = 0; kb < NB; ++kb) {
+          for (int kb = 0; kb < NB; ++kb)
             acc[a][kb] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b1[kb], acc[a][kb], 0, 0, 0);
-            acc[a][kb] = __builtin_amdgcn_mfma_f64_16x16x4f64(a2, b2[kb], acc[a][kb], 0, 0, 0);
+          if constexpr (TWO) {
+            const double a2 = sP2[(jb * 16 + lr) * kTLdx + col];
+#pragma unroll
+            for (int kb = 0; kb < NB; ++kb)
+              acc[a][kb] = __builtin_amdgcn_mfma_f64_16x16x4f64(a2, b2[kb], acc[a][kb], 0, 0, 0);
           }
         }
       }
     }
-    __syncthreads();
+    __syncthreads();  // every wave is done with the chunk before the next deposit
   }
   // accumulator item v of lane l: row lk + 4v, column lr of the 16 x 16 block
   if (wave >= NB) return;
@@ -1528,7 +1551,7 @@ hipError_t launch_zero_kpad(GemmPrec prec, int r, int ld, const OperandRef &o, h
 
 template <class O, int KS>
 static hipError_t launch_lops_t(int r, int ld, const double *g, const double *Xaa, const double *Xab,
-                                O Lp, O Lm, O L3, hipStream_t s) {
+                                O Lp, O Lm, O L3, double *fpart, hipStream_t s) {
   static int resident = 0;  // blocks the device holds at once
   constexpr int NR = ((4 * KS + 15) / 16) * 16;
   const int rp = lops_rp(KS);
@@ -1545,16 +1568,16 @@ static hipError_t launch_lops_t(int r, int ld, const double *g, const double *Xa
   }
   const int nslab = r * r;
   hipLaunchKernelGGL((k_lops<O, KS>), dim3(std::min(nslab, resident)), dim3(256), lds, s, r, ld, rp, g, Xaa,
-                     Xab, Lp, Lm, L3, nslab);
+                     Xab, Lp, Lm, L3, nslab, fpart);
   return hipGetLastError();
 }
 
 template <class O>
 static hipError_t launch_lops_o(int r, int ld, const double *g, const double *Xaa, const double *Xab, O Lp,
-                                O Lm, O L3, hipStream_t s) {
+                                O Lm, O L3, double *fpart, hipStream_t s) {
   switch ((r + 3) / 4) {
 #define ACSE_LOPS(K) \
-    case K: return launch_lops_t<O, K>(r, ld, g, Xaa, Xab, Lp, Lm, L3, s);
+    case K: return launch_lops_t<O, K>(r, ld, g, Xaa, Xab, Lp, Lm, L3, fpart, s);
     ACSE_LOPS(1) ACSE_LOPS(2) ACSE_LOPS(3) ACSE_LOPS(4) ACSE_LOPS(5) ACSE_LOPS(6) ACSE_LOPS(7)
     ACSE_LOPS(8) ACSE_LOPS(9) ACSE_LOPS(10) ACSE_LOPS(11) ACSE_LOPS(12) ACSE_LOPS(13) ACSE_LOPS(14)
 #undef ACSE_LOPS
@@ -1563,11 +1586,17 @@ static hipError_t launch_lops_o(int r, int ld, const double *g, const double *Xa
 }
 
 hipError_t launch_lops(GemmPrec prec, int r, int ld, const double *g, const double *Xaa, const double *Xab,
-                       const OperandRef &Lp, const OperandRef &Lm, const OperandRef &L3, hipStream_t s) {
+                       const OperandRef &Lp, const OperandRef &Lm, const OperandRef &L3, double *fpart,
+                       hipStream_t s) {
   if (r < 2 || r > kLopsMaxR) return hipErrorInvalidValue;
   ACSE_DISPATCH_OUT(prec, return launch_lops_o(r, ld, g, Xaa, Xab, make_out<O>(Lp), make_out<O>(Lm),
-                                               make_out<O>(L3), s));
+                                               make_out<O>(L3), fpart, s));
   return hipSuccess;
+}
+
+hipError_t launch_f_reduce(int r, const double *part, double *f, hipStream_t s) {
+  hipLaunchKernelGGL(k_f_reduce, dim3((unsigned)((r * r + 3) / 4)), dim3(256), 0, s, r, part, f);
+  return hipGetLastError();
 }
 
 hipError_t launch_f(int r, const double *Aaa, const double *Aab, const double *g, double *part,
@@ -1767,12 +1796,14 @@ static hipError_t launch_gram_nb(int r, const double *P1, const double *Q1, doub
                                  const double *P2, const double *Q2, double w2, double *part,
                                  hipStream_t s) {
   const size_t lds = (size_t)4 * NB * 16 * kTLdx * sizeof(double);
-  hipError_t err = hipFuncSetAttribute(reinterpret_cast<const void *>(&k_t_partial<NB>),
-                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-  if (err != hipSuccess) return err;
-  hipLaunchKernelGGL((k_t_partial<NB>), dim3(kTBlocks), dim3(256), lds, s, r, P1, Q1, P2, Q2, w1, w2,
-                     part);
-  return hipGetLastError();
+  auto go = [&](auto kern) -> hipError_t {
+    hipError_t err = hipFuncSetAttribute(reinterpret_cast<const void *>(kern),
+                                         hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (err != hipSuccess) return err;
+    hipLaunchKernelGGL(kern, dim3(kTBlocks), dim3(256), lds, s, r, P1, Q1, P2, Q2, w1, w2, part);
+    return hipGetLastError();
+  };
+  return P2 ? go(k_t_partial<NB, true>) : go(k_t_partial<NB, false>);
 }
 
 hipError_t launch_gram(int r, const double *P1, const double *Q1, double w1, const double *P2,
