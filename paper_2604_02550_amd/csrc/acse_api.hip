@@ -780,7 +780,7 @@ extern "C" acse_status acse_residual_vjp(acse_ctx ctx, const acse_problem *prob,
   auto contract = [&](std::initializer_list<ContractTerm> terms, double *out, int acc) -> hipError_t {
     ContractArgs a{};
     for (const ContractTerm &t : terms) a.term[a.nterms++] = t;
-    return launch_contract42(r, a, out, acc, s);
+    return launch_contract42(r, a, out, acc, w.tpart, s);
   };
 
   // ---------------- forward recompute (natural layouts) -------------------

@@ -32,7 +32,20 @@ struct ContractArgs {
   ContractTerm term[kMaxContractTerms];
   int nterms;
 };
-hipError_t launch_contract42(int r, const ContractArgs &a, double *out, int accumulate, hipStream_t s);
+// Terms with x, u in the first index pair of T and y, v in the second run as one
+// pass over the slabs of T with partial vectors in `part` (2 r^3 doubles);
+// other term patterns (or part == nullptr) take one block per output element.
+struct SlabTerm {
+  const double *T, *M;
+  double c;
+  int px, py;  // index positions of x (0 or 1) and y (2 or 3)
+};
+struct SlabContractArgs {
+  SlabTerm term[kMaxContractTerms];
+  int nterms;
+};
+hipError_t launch_contract42(int r, const ContractArgs &a, double *out, int accumulate, double *part,
+                             hipStream_t s);
 
 hipError_t launch_vjp_pe(int r, const double *Saa, const double *Sab, double *Ppb, double *Pmb,
                          double *E3b, hipStream_t s);
