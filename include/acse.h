@@ -26,8 +26,9 @@
  *              blocks encode): d2aa antisymmetric within (p,q) and within
  *              (r,s); d2ab[p,q,r,s] = d2ab[q,p,s,r] (the beta-alpha block is
  *              the pair-exchanged alpha-beta block).  The contractions exploit
- *              them and do not check them: other inputs give results that
- *              match no residual, with no error reported.
+ *              them and do not check them unless the options carry
+ *              ACSE_FLAG_CHECK_INPUTS: other inputs give results that match
+ *              no residual, with no error reported.
  *   R_aa, R_ab the residual blocks R(ia ja | ka la), R(ia jb | ka lb), same layout.
  *   ||R||^2    the squared Frobenius norm over all spin-orbital elements,
  *              2 ||R_aa||^2 + 4 ||R_ab||^2, taken before the active mask.
@@ -110,6 +111,17 @@ typedef struct {
  * order; meant for verifying those kernels at small r.  Other bits are an
  * ACSE_ERR_ARG. */
 #define ACSE_FLAG_GENERAL_KERNELS 1
+
+/* acse_options.flags: before computing, check on the device that the inputs
+ * have the symmetries the method requires of them (h and d1 symmetric; V
+ * invariant under p<->q, r<->s and (pq)<->(rs); d2aa antisymmetric under i<->j
+ * and k<->l and Hermitian; d2ab Hermitian and invariant under
+ * (ij)(kl) -> (ji)(lk)).  A largest violation above 1e-12 times the array's
+ * largest magnitude (or a non-finite value) returns ACSE_ERR_ARG naming the
+ * array; otherwise the call proceeds as without the flag.  Synchronises the
+ * stream.  Without the flag the symmetries are assumed, not checked: other
+ * inputs give results that are no residual of any state. */
+#define ACSE_FLAG_CHECK_INPUTS 2
 
 /* Creates a context on HIP device `device`, ordering work on `hip_stream`
  * (a hipStream_t; NULL = the default stream), with workspace for problems up

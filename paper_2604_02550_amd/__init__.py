@@ -55,6 +55,7 @@ class Options(ctypes.Structure):
 
 
 FLAG_GENERAL_KERNELS = 1
+FLAG_CHECK_INPUTS = 2
 
 
 _P = ctypes.c_void_p

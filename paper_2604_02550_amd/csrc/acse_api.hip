@@ -170,6 +170,38 @@ OperandRef operand(const Workspace &w, int idx, GemmPrec prec, int r) {
 }
 enum { OP_DAA, OP_DS, OP_DA, OP_BAA, OP_BS, OP_BA, OP_LP, OP_LM, OP_L3, OP_RP, OP_RM, OP_R3 };
 
+// ACSE_FLAG_CHECK_INPUTS: the largest violation of each input's required
+// symmetry, relative to the array's largest magnitude, must not exceed
+// kSymTol (synchronises; partials in the Gram scratch, results in scal[16..]).
+constexpr double kSymTol = 1e-12;
+
+acse_status check_inputs(acse_ctx c, const acse_problem *p, bool need_d1) {
+  HIP_TRY(c, hipSetDevice(c->device));
+  struct Item { const double *x; int kind; const char *name, *what; };
+  const Item items[5] = {
+      {p->h, 0, "h", "symmetric"},
+      {p->V, 1, "V", "invariant under p<->q, r<->s and (pq)<->(rs)"},
+      {p->d2aa, 2, "d2aa", "antisymmetric under i<->j and k<->l and invariant under (ij)<->(kl)"},
+      {p->d2ab, 3, "d2ab", "invariant under (ij)<->(kl) and (ij)(kl)->(ji)(lk)"},
+      {p->d1, 0, "d1", "symmetric"}};
+  const int n = need_d1 ? 5 : 4;
+  Workspace &w = c->ws;
+  for (int q = 0; q < n; ++q)
+    HIP_TRY(c, launch_sym_check(p->r, items[q].kind, items[q].x, w.tpart, w.scal + 16 + 2 * q, c->stream));
+  double host[10] = {};
+  HIP_TRY(c, hipMemcpyAsync(host, w.scal + 16, 2 * n * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+  HIP_TRY(c, hipStreamSynchronize(c->stream));
+  for (int q = 0; q < n; ++q) {
+    const double viol = host[2 * q], mag = host[2 * q + 1];
+    if (!(viol <= kSymTol * mag)) {
+      char buf[96];
+      std::snprintf(buf, sizeof buf, ": largest violation %.3e against largest magnitude %.3e", viol, mag);
+      return fail(c, ACSE_ERR_ARG, std::string(items[q].name) + " is not " + items[q].what + buf);
+    }
+  }
+  return ACSE_OK;
+}
+
 acse_status validate(acse_ctx c, const acse_problem *p, const acse_options *o, bool need_d1 = true) {
   if (!c) return ACSE_ERR_ARG;
   if (!p) return fail(c, ACSE_ERR_ARG, "problem is NULL");
@@ -191,9 +223,11 @@ acse_status validate(acse_ctx c, const acse_problem *p, const acse_options *o, b
       return fail(c, ACSE_ERR_ARG, "unknown precision");
     if (o->tile < -1 || o->tile >= gemm_num_tiles(GEMM_F64))
       return fail(c, ACSE_ERR_ARG, "tile configuration out of range");
-    if (o->flags & ~ACSE_FLAG_GENERAL_KERNELS) return fail(c, ACSE_ERR_ARG, "unknown option flags");
+    if (o->flags & ~(ACSE_FLAG_GENERAL_KERNELS | ACSE_FLAG_CHECK_INPUTS))
+      return fail(c, ACSE_ERR_ARG, "unknown option flags");
   }
   c->general = o && (o->flags & ACSE_FLAG_GENERAL_KERNELS);
+  if (o && (o->flags & ACSE_FLAG_CHECK_INPUTS)) return check_inputs(c, p, need_d1);
   return ACSE_OK;
 }
 

@@ -75,6 +75,10 @@ constexpr int kLopsMaxR = 56;
 hipError_t launch_lops(GemmPrec prec, int r, int ld, const double *g, const double *Xaa, const double *Xab,
                        const OperandRef &Lp, const OperandRef &Lm, const OperandRef &L3, double *fpart,
                        hipStream_t s);
+// Largest violation of an input symmetry and largest magnitude -> out2[0], out2[1]
+// (device); kind 0: symmetric r x r matrix, 1: (pq|rs) 8-fold, 2: alpha-alpha
+// 2-RDM, 3: alpha-beta 2-RDM.  part: 2048 doubles of scratch (the Gram partials hold 512 r^2 >= 2048).
+hipError_t launch_sym_check(int r, int kind, const double *x, double *part, double *out2, hipStream_t s);
 // f[k,s] = sum_p part[k,p,s] (the second half of launch_f, for partials from launch_lops).
 hipError_t launch_f_reduce(int r, const double *part, double *f, hipStream_t s);
 // G2 (natural FP64) and the packed pp B operands B_aa, B_S, B_A.

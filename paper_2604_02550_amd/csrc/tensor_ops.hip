@@ -1183,6 +1183,86 @@ k_reduce_sum(int64_t n, const double *__restrict__ part, double *__restrict__ ou
 }
 
 // ---------------------------------------------------------------------------
+// Input symmetry check: per block, the largest |x[e] - sign x[perm(e)]| over
+// the generators of the symmetry, and the largest |x[e]| (a NaN propagates
+// into both).  kind 0: r x r matrix, x[i,j] = x[j,i]; 1: (pq|rs), invariant
+// under p<->q, r<->s and (pq)<->(rs); 2: alpha-alpha 2-RDM, antisymmetric
+// under i<->j and k<->l, invariant under (ij)<->(kl); 3: alpha-beta 2-RDM,
+// invariant under (ij)<->(kl) and (ij)(kl) -> (ji)(lk).
+// ---------------------------------------------------------------------------
+__device__ inline double nan_max(double a, double b) { return (b > a || b != b) ? b : a; }
+
+__global__ void __launch_bounds__(256)
+k_sym_check(int r, int kind, const double *__restrict__ x, double *__restrict__ part) {
+  __shared__ double rv[256], rm[256];
+  const int64_t r2 = (int64_t)r * r;
+  const int64_t n = kind == 0 ? r2 : r2 * r2;
+  double viol = 0.0, mag = 0.0;
+  auto at = [&](int64_t a, int64_t b, int64_t c, int64_t d) { return x[((a * r + b) * r + c) * r + d]; };
+  for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < n; e += (int64_t)gridDim.x * 256) {
+    const double v = x[e];
+    mag = nan_max(mag, fabs(v));
+    if (kind == 0) {
+      const int64_t i = e / r, j = e % r;
+      viol = nan_max(viol, fabs(v - x[j * r + i]));
+      continue;
+    }
+    const int64_t l = e % r, kk = (e / r) % r, j = (e / r2) % r, i = e / (r2 * r);
+    const double sw = at(j, i, kk, l), sk = at(i, j, l, kk), ex = at(kk, l, i, j);
+    if (kind == 1) {
+      viol = nan_max(viol, fabs(v - sw));
+      viol = nan_max(viol, fabs(v - sk));
+      viol = nan_max(viol, fabs(v - ex));
+    } else if (kind == 2) {
+      viol = nan_max(viol, fabs(v + sw));
+      viol = nan_max(viol, fabs(v + sk));
+      viol = nan_max(viol, fabs(v - ex));
+    } else {
+      viol = nan_max(viol, fabs(v - ex));
+      viol = nan_max(viol, fabs(v - at(j, i, l, kk)));
+    }
+  }
+  rv[threadIdx.x] = viol;
+  rm[threadIdx.x] = mag;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if (threadIdx.x < w) {
+      rv[threadIdx.x] = nan_max(rv[threadIdx.x], rv[threadIdx.x + w]);
+      rm[threadIdx.x] = nan_max(rm[threadIdx.x], rm[threadIdx.x + w]);
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    part[2 * blockIdx.x] = rv[0];
+    part[2 * blockIdx.x + 1] = rm[0];
+  }
+}
+
+__global__ void __launch_bounds__(256)
+k_sym_reduce(int nb, const double *__restrict__ part, double *__restrict__ out) {
+  __shared__ double rv[256], rm[256];
+  double viol = 0.0, mag = 0.0;
+  for (int q = threadIdx.x; q < nb; q += 256) {
+    viol = nan_max(viol, part[2 * q]);
+    mag = nan_max(mag, part[2 * q + 1]);
+  }
+  rv[threadIdx.x] = viol;
+  rm[threadIdx.x] = mag;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if (threadIdx.x < w) {
+      rv[threadIdx.x] = nan_max(rv[threadIdx.x], rv[threadIdx.x + w]);
+      rm[threadIdx.x] = nan_max(rm[threadIdx.x], rm[threadIdx.x + w]);
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    out[0] = rv[0];
+    out[1] = rm[0];
+  }
+}
+
+// ---------------------------------------------------------------------------
 // Gram products  out[j,k] = sum_x (w1 P1[j,x] Q1[k,x] + w2 P2[j,x] Q2[k,x]),
 // x in [0, r^3) (for t: P = W, Q = A, weights 1 and 2).  A K-split over
 // kTBlocks blocks, each reducing its x range into an r x r partial on the FP64
@@ -1592,6 +1672,13 @@ hipError_t launch_lops(GemmPrec prec, int r, int ld, const double *g, const doub
   ACSE_DISPATCH_OUT(prec, return launch_lops_o(r, ld, g, Xaa, Xab, make_out<O>(Lp), make_out<O>(Lm),
                                                make_out<O>(L3), fpart, s));
   return hipSuccess;
+}
+
+hipError_t launch_sym_check(int r, int kind, const double *x, double *part, double *out2, hipStream_t s) {
+  constexpr int kNb = 1024;  // 2 kNb partial doubles
+  hipLaunchKernelGGL(k_sym_check, dim3(kNb), dim3(256), 0, s, r, kind, x, part);
+  hipLaunchKernelGGL(k_sym_reduce, dim3(1), dim3(256), 0, s, kNb, part, out2);
+  return hipGetLastError();
 }
 
 hipError_t launch_f_reduce(int r, const double *part, double *f, hipStream_t s) {

@@ -132,7 +132,7 @@ def test_unknown_option_flags_rejected(acse, ctx):
     prob, keep = ctx.problem(p["h"], p["V"], p["gamma"], p["d2aa"], p["d2ab"], p["N"] // 2)
     out = [keep[3].clone(), keep[4].clone()]
     with pytest.raises(acse.AcseError, match="flags"):
-        ctx.residual_raw(prob, ctx.options("fp64", flags=2), out[0], out[1])
+        ctx.residual_raw(prob, ctx.options("fp64", flags=4), out[0], out[1])
 
 
 def test_update_map_fp64(ctx):
@@ -209,3 +209,27 @@ def test_r30_mixed_precision_errors(ctx, r30, precision):
     assert errs["R_aa"] < tol["R"] and errs["R_ab"] < tol["R"]
     assert errs["U_aa"] < tol["U"] and errs["U_ab"] < tol["U"]
     assert de_rel < tol["dE_rel"]
+
+
+def test_input_symmetry_check(acse, ctx):
+    """ACSE_FLAG_CHECK_INPUTS: symmetric inputs pass and give the same residual
+    bitwise; a planted violation in each input array is reported by name."""
+    import torch
+    p = PROBLEMS["r6"]()
+    flag = acse.FLAG_CHECK_INPUTS
+    Raa, Rab, n2 = ctx.residual(p["h"], p["V"], p["gamma"], p["d2aa"], p["d2ab"], p["N"] // 2)
+    Caa, Cab, c2 = ctx.residual(p["h"], p["V"], p["gamma"], p["d2aa"], p["d2ab"], p["N"] // 2, flags=flag)
+    assert torch.equal(Raa, Caa) and torch.equal(Rab, Cab) and n2 == c2
+    names = {"h": "h", "V": "V", "gamma": "d1", "d2aa": "d2aa", "d2ab": "d2ab"}
+    for key, name in names.items():
+        q = {k: np.array(p[k], copy=True) for k in ("h", "V", "gamma", "d2aa", "d2ab")}
+        idx = (0, 1) if q[key].ndim == 2 else (0, 1, 2, 3)
+        q[key][idx] += 1e-6 * max(1.0, float(np.abs(q[key]).max()))
+        print(f"[symmetry check] planted in {key}", flush=True)
+        with pytest.raises(acse.AcseError, match=f"^.*: {name} is not"):
+            ctx.residual(q["h"], q["V"], q["gamma"], q["d2aa"], q["d2ab"], p["N"] // 2, flags=flag)
+    # the step checks too
+    q = {k: np.array(p[k], copy=True) for k in ("h", "V", "gamma", "d2aa", "d2ab")}
+    q["d2ab"][1, 0, 2, 3] += 1e-3
+    with pytest.raises(acse.AcseError, match="d2ab is not"):
+        ctx.step(q["h"], q["V"], q["gamma"], q["d2aa"], q["d2ab"], p["N"] // 2, flags=flag)
