@@ -55,6 +55,12 @@ def parse():
                     help="precisions of the adjoint (VJP) measurement ('' to skip)")
     ap.add_argument("--batched-modes", default="fp64,fp32",
                     help="precisions of the batched-instances measurement ('' to skip)")
+    ap.add_argument("--solve-controls", default="fixed,backtrack,quadratic",
+                    help="step controls of acse_solve timed on the workload (FP64); empty to skip")
+    ap.add_argument("--solve-iters", type=int, default=5)
+    ap.add_argument("--solve-eps", type=float, default=1e-5,
+                    help="first step size of the acse_solve leg (the synthetic r = 50 integrals are "
+                         "large: eps = 1e-3 raises ||R|| at the first trial)")
     ap.add_argument("--calibrate-copy-mib", type=int, default=0,
                     help="run one plain device copy of this many MiB (counter calibration)")
     return ap.parse_args()
@@ -171,6 +177,36 @@ def bench_vjp(acse, gen, torch, modes, steps, warmup):
         ctx.close()
         del keep, outs, R, Rb
         torch.cuda.empty_cache()
+    return res
+
+
+def bench_solve(acse, ctx, prob, work, pristine, torch, controls, iters, eps, step_ms):
+    """acse_solve (the Euler iteration with the method section's stopping rules)
+    on the headline workload, FP64, from the state whose 1-RDM is the
+    contraction of its 2-RDM (one acse_step with eps = 0 makes it so).  Wall
+    time per accepted step against the plain acse_step time: the driver's host
+    decisions, copies and per-trial synchronisations are the difference."""
+    opts = acse.Context.options("fp64")
+    res = {}
+    for control in controls:
+        for w, q in zip(work, pristine):
+            w.copy_(q)
+        ctx.step_raw(prob, 0.0, opts, want=False)
+        so = acse.SolveOptions(eps, 0.0, 0.0, iters, acse.CONTROLS[control], 8, 0)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        out, trials = ctx.solve_raw(prob, opts, so)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        res[control] = dict(iterations=out.iterations, trials=out.trials, maps=out.maps,
+                            stop=acse.STOP_REASONS[out.stop], wall_ms=wall * 1e3,
+                            ms_per_accepted_step=wall * 1e3 / max(1, out.iterations),
+                            ms_per_map=wall * 1e3 / max(1, out.maps),
+                            energy0=out.energy0, energy=out.energy,
+                            norm2_ratio=out.norm2 / out.norm2_0, eps_last=out.eps,
+                            eps0=eps, acse_step_ms=step_ms)
+    for w, q in zip(work, pristine):
+        w.copy_(q)
     return res
 
 
@@ -321,6 +357,9 @@ def main():
         "residual_only_evals_per_s": hr["residual_evals_per_s"],
         "modes": results,
     }
+    if args.solve_controls:
+        line["solve"] = bench_solve(acse, ctx, prob, work, pristine, torch, args.solve_controls.split(","),
+                                    args.solve_iters, args.solve_eps, results.get("fp64", hr)["ms_per_step"])
     if args.vjp_modes:
         line["vjp"] = bench_vjp(acse, gen, torch, args.vjp_modes.split(","), max(3, args.steps // 2),
                                 args.warmup)

@@ -162,6 +162,92 @@ acse_status acse_step(acse_ctx ctx, acse_problem *prob, double eps, const acse_o
                       double *R_aa, double *R_ab, double *U_aa, double *U_ab,
                       double *E_host, double *norm2_host);
 
+/* The Euler iteration of Eq. (9) with the stopping rules of the method
+ * section (fixed eps; stop when E or ||R|| rises, or when |dE| < 1e-6 Eh),
+ * driven on the host with every step on the device.
+ *
+ * Step n starts from the state 2D_n (with 1D_n, E_n, ||R_n||^2) and its update
+ * direction U_n = update_map(mask(R_n)).  A trial with step size x is
+ * 2D' = (2D_n + x U_n) rescaled per block to the trace of 2D_n, 1D' its
+ * contraction and E', ||R(2D')||^2 (before masking) its scalars.  A trial is
+ * acceptable iff E' <= E_n and ||R'||^2 <= ||R_n||^2.  Step-size control:
+ *   ACSE_EULER_FIXED      the method section's loop: the trial at eps is the
+ *                         step; a rise ends the iteration and the state before
+ *                         it is kept.
+ *   ACSE_EULER_BACKTRACK  a rise halves the step size (same U_n, new trial from
+ *                         2D_n) up to max_halvings times before ending; the step
+ *                         size of an accepted step carries over.
+ *   ACSE_EULER_QUADRATIC  Newton-like control from the adjoint: the slope
+ *                         f'(0) of f(x) = ||R(2D_n + x U_n)||^2 comes from
+ *                         acse_residual_vjp with the cotangent (4 R_aa, 8 R_ab)
+ *                         (the 1-RDM's dependence on 2D included); after the
+ *                         first trial at x = eps, if f'(0) < 0 the minimiser of
+ *                         f(0) + f'(0) x + c x^2 through f(eps) (4 eps if c <= 0),
+ *                         clamped to [eps/4, min(4 eps, eps_max)], is tried too
+ *                         unless within 5% of eps; the acceptable trial with the
+ *                         smaller ||R||^2 is taken (the first on a tie), else
+ *                         halving continues from the smaller step size.  Its
+ *                         step size carries over.
+ * After an accepted step, |E_{n+1} - E_n| < de_tol ends the iteration.
+ * Inputs whose 1D is not the contraction of 2D have it replaced by the
+ * contraction at the first accepted step (as in acse_step).
+ */
+typedef enum {
+  ACSE_EULER_FIXED = 0,
+  ACSE_EULER_BACKTRACK = 1,
+  ACSE_EULER_QUADRATIC = 2
+} acse_step_control;
+
+typedef enum {
+  ACSE_STOP_MAX_ITER = 0,     /* max_iter accepted steps taken */
+  ACSE_STOP_CONVERGED = 1,    /* the last accepted step changed E by less than de_tol */
+  ACSE_STOP_ENERGY_ROSE = 2,  /* the last trial raised E; the state before it is returned */
+  ACSE_STOP_NORM_ROSE = 3     /* the last trial raised ||R||; the state before it is returned */
+} acse_stop_reason;
+
+typedef struct {
+  double eps;            /* first step size (the method section uses 1e-3); finite, nonzero;
+                            > 0 for ACSE_EULER_QUADRATIC (a negative eps moves uphill) */
+  double de_tol;         /* energy-change threshold in Eh (the method section: 1e-6); >= 0 */
+  double eps_max;        /* ACSE_EULER_QUADRATIC: largest step size; 0 = 16 eps */
+  int32_t max_iter;      /* most accepted steps, >= 0 */
+  int32_t control;       /* acse_step_control */
+  int32_t max_halvings;  /* BACKTRACK, QUADRATIC: most halvings within one step, 0..60 */
+  int32_t reserved;      /* must be 0 */
+} acse_solve_options;
+
+typedef struct {
+  double eps;         /* step size of the trial */
+  double energy;      /* E of the trial 2-RDM */
+  double norm2;       /* ||R||^2 of the trial 2-RDM (before masking) */
+  int32_t step;       /* index n of the step the trial belongs to */
+  int32_t accepted;   /* 1 if the trial became 2D_{n+1} */
+} acse_trial;
+
+typedef struct {
+  double energy0, norm2_0;  /* E and ||R||^2 of the input state */
+  double energy, norm2;     /* of the returned state */
+  double eps;               /* step size of the last accepted step (0 if none) */
+  int32_t iterations;       /* accepted steps */
+  int32_t trials;           /* trials evaluated (all of them, also beyond the history capacity) */
+  int32_t maps;             /* residual maps F evaluated (residuals and update directions) */
+  int32_t stop;             /* acse_stop_reason */
+} acse_solve_result;
+
+/* Runs the iteration above on prob (1D, d2aa, d2ab overwritten with the
+ * returned state).  opts as for acse_step (precision of the contractions,
+ * active mask, tile, flags).  result (host) receives the summary; history
+ * (host, capacity entries, may be NULL if capacity is 0) receives the trials in
+ * order.  The first call allocates a driver workspace (2 r_max^2 + 1032
+ * doubles; 5 r_max^4 + 2 r_max^2 more for ACSE_EULER_QUADRATIC, which also
+ * allocates the adjoint workspace), kept until acse_destroy.  The state 2D_n is
+ * kept in the context's workspace while trials run.  Synchronises once per trial.  Errors as
+ * acse_step; bad solve options are ACSE_ERR_ARG; on an error mid-run the
+ * problem arrays hold the last accepted or trial state. */
+acse_status acse_solve(acse_ctx ctx, acse_problem *prob, const acse_options *opts,
+                       const acse_solve_options *sopts, acse_solve_result *result,
+                       acse_trial *history, int32_t capacity);
+
 /* Hand-written adjoint (vector-Jacobian product) of the residual of Eq. (4):
  * given a cotangent (Rbar_aa, Rbar_ab) on (R_aa, R_ab), writes the gradients of
  * L = <Rbar_aa, R_aa> + <Rbar_ab, R_ab> with respect to h, V, d1, d2aa and

@@ -1,0 +1,175 @@
+"""The Euler iteration of Eq. (9) with the method section's stopping rules,
+and two step-size controls (oracle; test infrastructure only).
+
+The method section propagates 2D_{n+1} = 2D_n + eps U_n with a fixed eps
+(1e-3 by default) and ends the iteration when the energy or the residual norm
+increases, or when the energy changes by less than 1e-6 Eh.
+
+Readings (the paper is silent on these points):
+
+* "Increase" compares the trial state with the current one: a trial 2D' is
+  acceptable iff E(2D') <= E_n and ||R(2D')||^2 <= ||R_n||^2 (the residual
+  norm over spin orbitals, before the active mask).  On an increase the
+  iteration ends and the state before the step is returned: the rise is not
+  kept.
+* The energy test is made after an accepted step: |E_{n+1} - E_n| < de_tol
+  ends the iteration with the new state.
+* BACKTRACK: instead of ending at a rise, eps is halved (the same U_n, a new
+  trial from 2D_n) at most ``max_halvings`` times; the step size of an
+  accepted step carries over to the next step.
+* QUADRATIC (Newton-like control from the adjoint): along the step,
+  f(eps) = ||R(2D_n + eps U_n)||^2 has the slope
+      f'(0) = <dbar_aa, U_aa> + <dbar_ab, U_ab> + <gbar, d gamma/d eps>,
+  where (gbar, dbar_aa, dbar_ab) is the vector-Jacobian product of the
+  residual map for the cotangent (4 R_aa, 8 R_ab) (the gradient of
+  2||R_aa||^2 + 4||R_ab||^2) and d gamma/d eps = 2/(N-1) Tr_2 U (the 1-RDM is
+  contracted from the 2-RDM after each step).  After the first trial at eps,
+  f is modelled as f(0) + f'(0) x + c x^2 through f(eps); when f'(0) < 0 the
+  model's minimiser (or 4 eps when c <= 0), clamped to [eps/4, min(4 eps,
+  eps_max)], is tried as well unless it lies within 5% of eps.  Of the
+  acceptable trials the one with the smaller f is kept (the first on a tie);
+  if neither is acceptable, plain halving continues from the smaller of the
+  two step sizes.
+* Trace restoration and the 1-RDM follow ``step.step``: each block is
+  rescaled to its trace before the step; gamma' = 2/(N-1) Tr_2 2D'.
+
+Every quantity is evaluated with the oracle's own residual, energy and
+adjoint; the GPU driver shares none of this code.
+"""
+import numpy as np
+
+from . import adjoint, rdm
+from .residual import residual_map
+from .step import active_mask
+
+FIXED, BACKTRACK, QUADRATIC = 0, 1, 2
+STOP_MAX_ITER, STOP_CONVERGED, STOP_ENERGY_ROSE, STOP_NORM_ROSE = 0, 1, 2, 3
+
+
+def _residual(K, gamma, d2aa, d2ab):
+    d1, d2 = rdm.blocks_to_spin_orbital(gamma, d2aa, d2ab)
+    R = residual_map(K, d1, d2, hermitian=True).numpy()
+    return R, float(np.sum(R ** 2)), d1, d2
+
+
+def _trial(K, N, d2aa, d2ab, uaa, uab, eps):
+    """2D' = (2D + eps U) rescaled per block to the trace of 2D; gamma'; E'."""
+    r = d2aa.shape[0]
+    a = d2aa + eps * uaa
+    b = d2ab + eps * uab
+    t0aa, t0ab = rdm.block_traces(d2aa, d2ab)
+    t1aa, t1ab = rdm.block_traces(a, b)
+    a = a * (t0aa / t1aa)
+    b = b * (t0ab / t1ab)
+    _, d2 = rdm.blocks_to_spin_orbital(np.eye(r), a, b)
+    gamma = rdm.contract_to_1rdm(d2, N)[:r, :r]
+    return a, b, gamma, float(np.sum(K * d2))
+
+
+def norm_slope(h, V, N, gamma, d2aa, d2ab, Raa, Rab, uaa, uab):
+    """f'(0) for f(eps) = ||R(2D + eps U)||^2 over spin orbitals, from the
+    residual's vector-Jacobian product (cotangent 4 R_aa, 8 R_ab)."""
+    r = h.shape[0]
+    g = adjoint.residual_vjp(h, V, N, gamma, d2aa, d2ab, 4.0 * Raa, 8.0 * Rab)
+    _, u = rdm.blocks_to_spin_orbital(np.zeros((r, r)), uaa, uab)
+    dgamma = rdm.contract_to_1rdm(u, N)[:r, :r]
+    return float(np.sum(g["d2aa"] * uaa) + np.sum(g["d2ab"] * uab) + np.sum(g["gamma"] * dgamma))
+
+
+def quadratic_trial_step(f0, g0, eps, f_eps, eps_max):
+    """Second step size of QUADRATIC, or None: the minimiser of the parabola
+    through f(0) = f0 with slope g0 and f(eps) = f_eps, clamped to
+    [eps/4, min(4 eps, eps_max)]; 4 eps (clamped) when the curvature is not
+    positive.  None when g0 >= 0 or the result is within 5% of eps."""
+    if not g0 < 0.0:
+        return None
+    c = (f_eps - f0 - g0 * eps) / (eps * eps)
+    hi = min(4.0 * eps, eps_max)
+    x = -g0 / (2.0 * c) if c > 0.0 else hi
+    x = min(max(x, 0.25 * eps), hi)
+    if abs(x - eps) <= 0.05 * abs(eps):
+        return None
+    return x
+
+
+def euler(h, V, N, gamma, d2aa, d2ab, eps=1e-3, de_tol=1e-6, max_iter=100, control=FIXED,
+          max_halvings=8, eps_max=0.0, active=None):
+    """Run the iteration; returns a dict with the final gamma, d2aa, d2ab, the
+    energies and norms of the input and returned states, the stop reason, the
+    accepted-step count and the list of trials (eps, E, ||R||^2, step index,
+    accepted)."""
+    h = np.asarray(h, dtype=np.float64)
+    V = np.asarray(V, dtype=np.float64)
+    r = h.shape[0]
+    K = rdm.reduced_hamiltonian(h, V, N)
+    mask = active_mask(active, r)
+    eps_max = eps_max if eps_max > 0.0 else 16.0 * abs(eps)
+    gamma = np.array(gamma, dtype=np.float64)
+    d2aa = np.array(d2aa, dtype=np.float64)
+    d2ab = np.array(d2ab, dtype=np.float64)
+    _, d2 = rdm.blocks_to_spin_orbital(gamma, d2aa, d2ab)
+    E = float(np.sum(K * d2))
+    R, f, d1, d2 = _residual(K, gamma, d2aa, d2ab)
+    out = dict(energy0=E, norm2_0=f, trials=[], iterations=0, stop=STOP_MAX_ITER, eps_last=0.0)
+    e = eps
+
+    def ok(Et, ft):
+        return Et <= E and ft <= f
+
+    def why(Et):
+        return STOP_ENERGY_ROSE if Et > E else STOP_NORM_ROSE
+
+    for n in range(max_iter):
+        Rm = R if mask is None else R * mask
+        U = residual_map(Rm, d1, d2, hermitian=False).numpy()
+        uaa, uab = rdm.spin_orbital_to_blocks(U)
+        raa, rab = rdm.spin_orbital_to_blocks(R)
+
+        def run(x):
+            a, b, g1, Et = _trial(K, N, d2aa, d2ab, uaa, uab, x)
+            Rt, ft, _, _ = _residual(K, g1, a, b)
+            return dict(eps=x, d2aa=a, d2ab=b, gamma=g1, E=Et, f=ft, R=Rt)
+
+        trials = []
+
+        def attempt(x):
+            q = run(x)
+            trials.append(q)
+            return q
+
+        t = attempt(e)
+        chosen = t if ok(t["E"], t["f"]) else None
+        cand = e
+        if control == QUADRATIC:
+            g0 = norm_slope(h, V, N, gamma, d2aa, d2ab, raa, rab, uaa, uab)
+            x = quadratic_trial_step(f, g0, e, t["f"], eps_max)
+            if x is not None:
+                t2 = attempt(x)
+                good = [q for q in (t, t2) if ok(q["E"], q["f"])]
+                chosen = min(good, key=lambda q: q["f"]) if good else None  # first on a tie
+                cand = min(e, x)
+        halvings = 0
+        while chosen is None and control != FIXED and halvings < max_halvings:
+            cand = 0.5 * cand
+            halvings += 1
+            t = attempt(cand)
+            if ok(t["E"], t["f"]):
+                chosen = t
+        stop = None if chosen is not None else why(trials[-1]["E"])
+        for q in trials:
+            out["trials"].append((q["eps"], q["E"], q["f"], n, q is chosen))
+        if chosen is None:
+            out["stop"] = stop
+            break
+        dE = chosen["E"] - E
+        d2aa, d2ab, gamma = chosen["d2aa"], chosen["d2ab"], chosen["gamma"]
+        E, f, R = chosen["E"], chosen["f"], chosen["R"]
+        d1, d2 = rdm.blocks_to_spin_orbital(gamma, d2aa, d2ab)
+        e = chosen["eps"]
+        out["iterations"] = n + 1
+        out["eps_last"] = e
+        if abs(dE) < de_tol:
+            out["stop"] = STOP_CONVERGED
+            break
+    out.update(gamma=gamma, d2aa=d2aa, d2ab=d2ab, energy=E, norm2=f)
+    return out

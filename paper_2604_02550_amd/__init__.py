@@ -33,7 +33,7 @@ EXPORTS = ("acse_create", "acse_destroy", "acse_set_stream", "acse_residual", "a
            "acse_energy", "acse_step", "acse_status_str", "acse_last_error",
            "acse_workspace_bytes", "acse_profile_enable", "acse_profile_read", "acse_autotune",
            "acse_residual_vjp", "acse_energy_vjp", "acse_residual_batched",
-           "acse_autotune_batched")
+           "acse_autotune_batched", "acse_solve")
 NUM_TILE_CONFIGS = 3
 NUM_STAGES = 6
 STAGES = ("rdm_operands", "fold", "transforms", "gemm", "assembly", "step_tail")
@@ -56,6 +56,28 @@ class Options(ctypes.Structure):
 
 FLAG_GENERAL_KERNELS = 1
 FLAG_CHECK_INPUTS = 2
+
+EULER_FIXED, EULER_BACKTRACK, EULER_QUADRATIC = 0, 1, 2
+CONTROLS = {"fixed": EULER_FIXED, "backtrack": EULER_BACKTRACK, "quadratic": EULER_QUADRATIC}
+STOP_REASONS = ("max_iter", "converged", "energy_rose", "norm_rose")
+
+
+class SolveOptions(ctypes.Structure):
+    _fields_ = [("eps", ctypes.c_double), ("de_tol", ctypes.c_double), ("eps_max", ctypes.c_double),
+                ("max_iter", ctypes.c_int32), ("control", ctypes.c_int32),
+                ("max_halvings", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+
+
+class Trial(ctypes.Structure):
+    _fields_ = [("eps", ctypes.c_double), ("energy", ctypes.c_double), ("norm2", ctypes.c_double),
+                ("step", ctypes.c_int32), ("accepted", ctypes.c_int32)]
+
+
+class SolveResult(ctypes.Structure):
+    _fields_ = [("energy0", ctypes.c_double), ("norm2_0", ctypes.c_double),
+                ("energy", ctypes.c_double), ("norm2", ctypes.c_double), ("eps", ctypes.c_double),
+                ("iterations", ctypes.c_int32), ("trials", ctypes.c_int32), ("maps", ctypes.c_int32),
+                ("stop", ctypes.c_int32)]
 
 
 _P = ctypes.c_void_p
@@ -87,6 +109,9 @@ _sig = {
     "acse_autotune_batched": (ctypes.c_int, [_P, ctypes.c_int32, ctypes.POINTER(Problem),
                                              ctypes.POINTER(Options), ctypes.POINTER(ctypes.c_int32),
                                              _D]),
+    "acse_solve": (ctypes.c_int, [_P, ctypes.POINTER(Problem), ctypes.POINTER(Options),
+                                  ctypes.POINTER(SolveOptions), ctypes.POINTER(SolveResult),
+                                  ctypes.POINTER(Trial), ctypes.c_int32]),
 }
 for _name, (_res, _args) in _sig.items():
     _fn = getattr(_lib, _name)
@@ -243,6 +268,32 @@ class Context:
         if return_ru:
             extra = dict(R_aa=bufs[0], R_ab=bufs[1], U_aa=bufs[2], U_ab=bufs[3])
         return dict(d1=t[2], d2aa=t[3], d2ab=t[4], energy=E, norm2=n2, **extra)
+
+    def solve_raw(self, prob, opts, sopts, capacity=256):
+        """acse_solve on a prepared problem; returns (SolveResult, [Trial])."""
+        res = SolveResult()
+        hist = (Trial * max(1, capacity))()
+        self._check(_lib.acse_solve(self._h, ctypes.byref(prob), ctypes.byref(opts), ctypes.byref(sopts),
+                                    ctypes.byref(res), hist, int(capacity)))
+        return res, [hist[i] for i in range(min(res.trials, capacity))]
+
+    def solve(self, h, V, d1, d2aa, d2ab, n_alpha, eps=1e-3, de_tol=1e-6, max_iter=100,
+              control="fixed", max_halvings=8, eps_max=0.0, precision="fp64", active=None, tile=-1,
+              flags=0, capacity=256):
+        """The Euler iteration of Eq. (9) with the stopping rules of the method
+        section on device copies of the inputs (acse_solve).  Returns a dict with
+        the final d1, d2aa, d2ab (device), energy/norm2 of the input and returned
+        states, iterations, maps, the stop reason, the last accepted step size and
+        the trials as (eps, energy, norm2, step, accepted) tuples."""
+        prob, t = self.problem(h, V, d1, d2aa, d2ab, n_alpha)
+        so = SolveOptions(float(eps), float(de_tol), float(eps_max), int(max_iter),
+                          CONTROLS[control] if isinstance(control, str) else int(control),
+                          int(max_halvings), 0)
+        res, hist = self.solve_raw(prob, self.options(precision, active, tile, flags), so, capacity)
+        return dict(d1=t[2], d2aa=t[3], d2ab=t[4], energy0=res.energy0, norm2_0=res.norm2_0,
+                    energy=res.energy, norm2=res.norm2, eps=res.eps, iterations=res.iterations,
+                    trial_count=res.trials, maps=res.maps, stop=STOP_REASONS[res.stop],
+                    trials=[(q.eps, q.energy, q.norm2, q.step, bool(q.accepted)) for q in hist])
 
     def residual_vjp_raw(self, prob, opts, Rbar_aa, Rbar_ab, h_bar, V_bar, d1_bar, d2aa_bar, d2ab_bar):
         self._check(_lib.acse_residual_vjp(self._h, ctypes.byref(prob), ctypes.byref(opts),

@@ -88,6 +88,9 @@ struct acse_ctx_s {
   double *vnat[36] = {};
   char *vop[12] = {};
   double *vsmall = nullptr;  // gb, tb, fb, I, hb_raw (r_max^2 each)
+  // Euler driver workspace (allocated by the first acse_solve call)
+  void *sbase = nullptr;
+  int64_t sbytes = 0;
 };
 
 namespace {
@@ -531,6 +534,7 @@ acse_status acse_destroy(acse_ctx ctx) {
   for (auto &q : ctx->recs) { (void)hipEventDestroy(q.a); (void)hipEventDestroy(q.b); }
   for (auto e : ctx->pool) (void)hipEventDestroy(e);
   if (ctx->vbase) (void)hipFree(ctx->vbase);
+  if (ctx->sbase) (void)hipFree(ctx->sbase);
   if (ctx->bbase) (void)hipFree(ctx->bbase);
   if (ctx->hdesc) (void)hipHostFree(ctx->hdesc);
   if (ctx->hdesc_done) (void)hipEventDestroy(ctx->hdesc_done);
@@ -1072,6 +1076,263 @@ extern "C" acse_status acse_energy_vjp(acse_ctx ctx, const acse_problem *prob, d
   HIP_TRY(ctx, launch_vjp_fold(r, N, zero, D, Vraw, hb_raw, s));
   HIP_TRY(ctx, launch_proj(PROJ_V, r, 1.0, Vraw, V_bar, s));
   HIP_TRY(ctx, launch_proj(PROJ_SYM2, r, 1.0, hb_raw, h_bar, s));
+  return ACSE_OK;
+}
+
+// ===========================================================================
+// Euler iteration of Eq. (9) with the stopping rules of the method section and
+// the step-size controls declared with acse_solve.  The host makes every
+// decision from the FP64 scalars (E, ||R||^2) of each trial; all array work
+// stays on the device.
+// ===========================================================================
+namespace {
+
+struct SolveWs {
+  double *g_keep, *dgamma, *dots, *part;        // r^2, r^2, 8, kDotBlocks
+  double *Rbar_aa, *Rbar_ab, *Vbar, *Dbar_aa, *Dbar_ab, *hbar, *gbar;  // QUADRATIC only
+};
+
+acse_status ensure_solve_ws(acse_ctx c, bool quadratic, SolveWs &sw) {
+  const int64_t r2 = (int64_t)c->r_max * c->r_max;
+  const int64_t n4 = r2 * r2;
+  const int64_t small = 2 * round_up(r2 * 8, 256) + round_up(8 * 8, 256) + round_up(kDotBlocks * 8, 256);
+  const int64_t big = 5 * round_up(n4 * 8, 256) + 2 * round_up(r2 * 8, 256);
+  const int64_t need = small + (quadratic ? big : 0);
+  if (c->sbytes < need) {
+    if (c->sbase) {
+      HIP_TRY(c, hipStreamSynchronize(c->stream));
+      (void)hipFree(c->sbase);
+      c->sbase = nullptr;
+      c->sbytes = 0;
+    }
+    if (hipMalloc(&c->sbase, need) != hipSuccess) {
+      (void)hipGetLastError();
+      c->sbase = nullptr;
+      return fail(c, ACSE_ERR_NOMEM, "driver workspace allocation failed");
+    }
+    c->sbytes = need;
+  }
+  char *p = static_cast<char *>(c->sbase);
+  auto take = [&](int64_t bytes) {
+    double *x = reinterpret_cast<double *>(p);
+    p += round_up(bytes, 256);
+    return x;
+  };
+  sw = SolveWs{};
+  sw.g_keep = take(r2 * 8);
+  sw.dgamma = take(r2 * 8);
+  sw.dots = take(8 * 8);
+  sw.part = take(kDotBlocks * 8);
+  if (quadratic) {
+    sw.Rbar_aa = take(n4 * 8);
+    sw.Rbar_ab = take(n4 * 8);
+    sw.Vbar = take(n4 * 8);
+    sw.Dbar_aa = take(n4 * 8);
+    sw.Dbar_ab = take(n4 * 8);
+    sw.hbar = take(r2 * 8);
+    sw.gbar = take(r2 * 8);
+  }
+  return ACSE_OK;
+}
+
+acse_status check_solve_options(acse_ctx c, const acse_solve_options *so, const acse_solve_result *res,
+                                const acse_trial *hist, int32_t cap) {
+  if (!so) return fail(c, ACSE_ERR_ARG, "solve options are NULL");
+  if (!res) return fail(c, ACSE_ERR_ARG, "result is NULL");
+  if (cap < 0 || (cap > 0 && !hist)) return fail(c, ACSE_ERR_ARG, "history capacity > 0 needs a history array");
+  if (!std::isfinite(so->eps) || so->eps == 0.0) return fail(c, ACSE_ERR_ARG, "eps must be finite and nonzero");
+  if (!std::isfinite(so->de_tol) || so->de_tol < 0.0) return fail(c, ACSE_ERR_ARG, "de_tol must be finite and >= 0");
+  if (!std::isfinite(so->eps_max) || so->eps_max < 0.0) return fail(c, ACSE_ERR_ARG, "eps_max must be finite and >= 0");
+  if (so->max_iter < 0) return fail(c, ACSE_ERR_ARG, "max_iter must be >= 0");
+  if (so->control < ACSE_EULER_FIXED || so->control > ACSE_EULER_QUADRATIC)
+    return fail(c, ACSE_ERR_ARG, "unknown step control");
+  if (so->max_halvings < 0 || so->max_halvings > 60) return fail(c, ACSE_ERR_ARG, "max_halvings must be in [0, 60]");
+  if (so->control == ACSE_EULER_QUADRATIC && !(so->eps > 0.0))
+    return fail(c, ACSE_ERR_ARG, "the quadratic control needs eps > 0");
+  if (so->reserved != 0) return fail(c, ACSE_ERR_ARG, "reserved must be 0");
+  return ACSE_OK;
+}
+
+// Second step size of the quadratic control, or 0 for none: the minimiser of
+// the parabola through f(0) = f0 with slope g0 and f(x) = fx, clamped to
+// [x/4, min(4x, xmax)] (4x, clamped, for a non-positive curvature); none for
+// g0 >= 0 or a result within 5% of x.
+double quadratic_second_step(double f0, double g0, double x, double fx, double xmax) {
+  if (!(g0 < 0.0)) return 0.0;
+  const double c = (fx - f0 - g0 * x) / (x * x);
+  const double hi = std::min(4.0 * x, xmax);
+  double y = c > 0.0 ? -g0 / (2.0 * c) : hi;
+  y = std::min(std::max(y, 0.25 * x), hi);
+  return std::fabs(y - x) <= 0.05 * std::fabs(x) ? 0.0 : y;
+}
+
+}  // namespace
+
+extern "C" acse_status acse_solve(acse_ctx ctx, acse_problem *prob, const acse_options *opts,
+                                  const acse_solve_options *so, acse_solve_result *res,
+                                  acse_trial *hist, int32_t cap) {
+  acse_status st = validate(ctx, prob, opts);
+  if (st != ACSE_OK) return st;
+  if ((st = check_solve_options(ctx, so, res, hist, cap)) != ACSE_OK) return st;
+  HIP_TRY(ctx, hipSetDevice(ctx->device));
+  const bool quad = so->control == ACSE_EULER_QUADRATIC;
+  SolveWs sw{};
+  if ((st = ensure_solve_ws(ctx, quad, sw)) != ACSE_OK) return st;
+  if (quad && (st = ensure_vjp_ws(ctx)) != ACSE_OK) return st;
+
+  Workspace &w = ctx->ws;
+  hipStream_t s = ctx->stream;
+  const int r = prob->r;
+  const int N = prob->n_alpha + prob->n_beta;
+  const int64_t r2 = (int64_t)r * r, n4 = r2 * r2;
+  const GemmPrec prec = prec_of(opts);
+  const int cfg = opts ? opts->tile : -1;
+  bool masked = false;
+  const ActiveBits act = make_bits(opts, r, &masked);
+  const double eps_max = so->eps_max > 0.0 ? so->eps_max : 16.0 * std::fabs(so->eps);
+  // the adjoint calls run without the input check (done once above)
+  acse_options vopt{};
+  if (opts) vopt = *opts;
+  vopt.active = nullptr;
+  vopt.flags &= ~ACSE_FLAG_CHECK_INPUTS;
+
+  *res = acse_solve_result{};
+  auto record = [&](double x, double E, double f, int n) -> int32_t {
+    const int32_t id = res->trials++;
+    if (id < cap) hist[id] = acse_trial{x, E, f, n, 0};
+    return id;
+  };
+  auto mark = [&](int32_t id) { if (id >= 0 && id < cap) hist[id].accepted = 1; };
+  // residual of the current problem arrays into w.Raa/Rab (masked copy into M)
+  auto residual = [&](double *f, double *E) -> acse_status {
+    acse_status q;
+    if ((q = prep_rdm_operands(ctx, prob, prec)) != ACSE_OK) return q;
+    if ((q = run_map(ctx, prob, prec, cfg, w.Aaa, w.Aab, -1.0, w.Raa, w.Rab, act, masked ? w.Maa : nullptr,
+                     masked ? w.Mab : nullptr, 0)) != ACSE_OK)
+      return q;
+    ++res->maps;
+    return fetch_scalars(ctx, f, E);
+  };
+  // trial 2D' = rescaled(2D_n + x U_n) from the kept 2D_n, its 1-RDM, E' and ||R'||^2
+  auto trial = [&](double x, bool restore, double *f, double *E) -> acse_status {
+    if (restore) {
+      HIP_TRY(ctx, hipMemcpyAsync(prob->d2aa, w.Naa, n4 * 8, hipMemcpyDeviceToDevice, s));
+      HIP_TRY(ctx, hipMemcpyAsync(prob->d2ab, w.Nab, n4 * 8, hipMemcpyDeviceToDevice, s));
+    }
+    {
+      StageTimer t5(ctx, 5);
+      HIP_TRY(ctx, launch_step_tail(r, N, x, prob->h, prob->V, w.Uaa, w.Uab, prob->d2aa, prob->d2ab,
+                                    w.scal + 4, w.partial, w.scal + 1, s));
+      HIP_TRY(ctx, launch_contract_1rdm(r, N, prob->d2aa, prob->d2ab, prob->d1, s));
+    }
+    return residual(f, E);
+  };
+
+  {
+    StageTimer t1(ctx, 1);
+    HIP_TRY(ctx, launch_fold(r, N, prob->h, prob->V, w.Aaa, w.Aab, s));
+  }
+  {
+    StageTimer t5(ctx, 5);
+    HIP_TRY(ctx, launch_energy(r, N, prob->h, prob->V, prob->d2aa, prob->d2ab, w.partial, w.scal + 1, s));
+  }
+  double E = 0.0, f = 0.0;
+  if ((st = residual(&f, &E)) != ACSE_OK) return st;
+  res->energy0 = res->energy = E;
+  res->norm2_0 = res->norm2 = f;
+  res->stop = ACSE_STOP_MAX_ITER;
+  double e = so->eps;
+
+  for (int n = 0; n < so->max_iter; ++n) {
+    // U_n = F(R_m) with the operands of 2D_n
+    if ((st = run_map(ctx, prob, prec, cfg, masked ? w.Maa : w.Raa, masked ? w.Mab : w.Rab, +1.0, w.Uaa,
+                      w.Uab, ActiveBits{}, nullptr, nullptr, 2)) != ACSE_OK)
+      return st;
+    ++res->maps;
+    double g0 = 0.0;
+    if (quad) {
+      // f'(0) = <Dbar_aa, U_aa> + <Dbar_ab, U_ab> + <gbar, dgamma>, cotangent (4 R_aa, 8 R_ab)
+      HIP_TRY(ctx, launch_scale2(n4, 4.0, w.Raa, 8.0, w.Rab, sw.Rbar_aa, sw.Rbar_ab, s));
+      if ((st = acse_residual_vjp(ctx, prob, &vopt, sw.Rbar_aa, sw.Rbar_ab, sw.hbar, sw.Vbar, sw.gbar,
+                                  sw.Dbar_aa, sw.Dbar_ab)) != ACSE_OK)
+        return st;
+      HIP_TRY(ctx, launch_contract_1rdm(r, N, w.Uaa, w.Uab, sw.dgamma, s));
+      HIP_TRY(ctx, launch_dot(n4, sw.Dbar_aa, w.Uaa, sw.part, sw.dots + 0, s));
+      HIP_TRY(ctx, launch_dot(n4, sw.Dbar_ab, w.Uab, sw.part, sw.dots + 1, s));
+      HIP_TRY(ctx, launch_dot(r2, sw.gbar, sw.dgamma, sw.part, sw.dots + 2, s));
+      double d[3] = {0.0, 0.0, 0.0};
+      HIP_TRY(ctx, hipMemcpyAsync(d, sw.dots, sizeof d, hipMemcpyDeviceToHost, s));
+      HIP_TRY(ctx, hipStreamSynchronize(s));
+      g0 = d[0] + d[1] + d[2];
+      if (!std::isfinite(g0)) return fail(ctx, ACSE_ERR_NONFINITE, "slope of ||R||^2 is not finite");
+      StageTimer t1(ctx, 1);  // the adjoint reuses the fold's buffers
+      HIP_TRY(ctx, launch_fold(r, N, prob->h, prob->V, w.Aaa, w.Aab, s));
+    }
+    // keep 2D_n and 1D_n
+    HIP_TRY(ctx, hipMemcpyAsync(w.Naa, prob->d2aa, n4 * 8, hipMemcpyDeviceToDevice, s));
+    HIP_TRY(ctx, hipMemcpyAsync(w.Nab, prob->d2ab, n4 * 8, hipMemcpyDeviceToDevice, s));
+    HIP_TRY(ctx, hipMemcpyAsync(sw.g_keep, prob->d1, r2 * 8, hipMemcpyDeviceToDevice, s));
+
+    auto ok = [&](double Et, double ft) { return Et <= E && ft <= f; };
+    double x1 = e, f1 = 0.0, E1 = 0.0;
+    if ((st = trial(x1, false, &f1, &E1)) != ACSE_OK) return st;
+    int32_t id1 = record(x1, E1, f1, n);
+    bool chosen = ok(E1, f1);
+    double xc = x1, fc = f1, Ec = E1;  // chosen trial (valid if chosen)
+    int32_t idc = id1;
+    double last_E = E1;
+    double cand = e;
+    if (quad) {
+      const double x2 = quadratic_second_step(f, g0, x1, f1, eps_max);
+      if (x2 != 0.0) {
+        double f2 = 0.0, E2 = 0.0;
+        if ((st = trial(x2, true, &f2, &E2)) != ACSE_OK) return st;
+        const int32_t id2 = record(x2, E2, f2, n);
+        last_E = E2;
+        const bool ok1 = ok(E1, f1), ok2 = ok(E2, f2);
+        if (ok2 && (!ok1 || f2 < f1)) {
+          chosen = true; xc = x2; fc = f2; Ec = E2; idc = id2;
+        } else if (ok1) {
+          // the arrays hold the second trial: evaluate the first again (same kernels, same values)
+          if ((st = trial(x1, true, &f1, &E1)) != ACSE_OK) return st;
+          chosen = true; xc = x1; fc = f1; Ec = E1; idc = id1;
+        } else {
+          chosen = false;
+        }
+        cand = std::min(x1, x2);
+      }
+    }
+    for (int hv = 0; !chosen && so->control != ACSE_EULER_FIXED && hv < so->max_halvings; ++hv) {
+      cand *= 0.5;
+      double ft = 0.0, Et = 0.0;
+      if ((st = trial(cand, true, &ft, &Et)) != ACSE_OK) return st;
+      const int32_t id = record(cand, Et, ft, n);
+      last_E = Et;
+      if (ok(Et, ft)) { chosen = true; xc = cand; fc = ft; Ec = Et; idc = id; }
+    }
+    if (!chosen) {
+      // keep the state before the rise
+      HIP_TRY(ctx, hipMemcpyAsync(prob->d2aa, w.Naa, n4 * 8, hipMemcpyDeviceToDevice, s));
+      HIP_TRY(ctx, hipMemcpyAsync(prob->d2ab, w.Nab, n4 * 8, hipMemcpyDeviceToDevice, s));
+      HIP_TRY(ctx, hipMemcpyAsync(prob->d1, sw.g_keep, r2 * 8, hipMemcpyDeviceToDevice, s));
+      HIP_TRY(ctx, hipStreamSynchronize(s));
+      res->stop = last_E > E ? ACSE_STOP_ENERGY_ROSE : ACSE_STOP_NORM_ROSE;
+      break;
+    }
+    mark(idc);
+    const double dE = Ec - E;
+    E = Ec;
+    f = fc;
+    e = xc;
+    res->iterations = n + 1;
+    res->eps = xc;
+    res->energy = E;
+    res->norm2 = f;
+    if (std::fabs(dE) < so->de_tol) {
+      res->stop = ACSE_STOP_CONVERGED;
+      break;
+    }
+  }
   return ACSE_OK;
 }
 

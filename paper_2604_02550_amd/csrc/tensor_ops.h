@@ -129,5 +129,12 @@ hipError_t launch_rescale(int r, const double *traces, const double *naa, const 
 hipError_t launch_contract_1rdm(int r, int N, const double *d2aa, const double *d2ab, double *g,
                                 hipStream_t s);
 hipError_t launch_fill(int64_t n, double v, double *p, hipStream_t s);
+// oa = ca a, ob = cb b (n elements each).
+hipError_t launch_scale2(int64_t n, double ca, const double *a, double cb, const double *b, double *oa,
+                         double *ob, hipStream_t s);
+// out[0] = sum_e a[e] b[e] in a fixed order (part: kDotBlocks doubles of scratch).
+constexpr int kDotBlocks = 1024;
+hipError_t launch_dot(int64_t n, const double *a, const double *b, double *part, double *out,
+                      hipStream_t s);
 
 }  // namespace acse

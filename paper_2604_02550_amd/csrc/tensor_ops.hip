@@ -1559,6 +1559,33 @@ __global__ void k_fill(int64_t n, double v, double *__restrict__ p) {
   if (e < n) p[e] = v;
 }
 
+// oa = ca a, ob = cb b over n elements.
+__global__ void k_scale2(int64_t n, double ca, const double *__restrict__ a, double cb,
+                         const double *__restrict__ b, double *__restrict__ oa, double *__restrict__ ob) {
+  const int64_t e = gtid();
+  if (e >= n) return;
+  oa[e] = ca * a[e];
+  ob[e] = cb * b[e];
+}
+
+// Partial sums of a[e] b[e]: block q takes the grid-strided elements of its
+// threads and leaves one partial in part[q] (fixed order: deterministic).
+__global__ void __launch_bounds__(256)
+k_dot_partial(int64_t n, const double *__restrict__ a, const double *__restrict__ b,
+              double *__restrict__ part) {
+  __shared__ double red[256];
+  double acc = 0.0;
+  for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < n; e += (int64_t)gridDim.x * 256)
+    acc = fma(a[e], b[e], acc);
+  red[threadIdx.x] = acc;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) part[blockIdx.x] = red[0];
+}
+
 // ---------------------------------------------------------------------------
 // Host launchers
 // ---------------------------------------------------------------------------
@@ -1961,6 +1988,21 @@ hipError_t launch_contract_1rdm(int r, int N, const double *d2aa, const double *
                                 hipStream_t s) {
   hipLaunchKernelGGL(k_contract_1rdm, dim3((unsigned)((r * r + 3) / 4)), dim3(256), 0, s, r, 2.0 / (N - 1),
                      d2aa, d2ab, g);
+  return hipGetLastError();
+}
+
+hipError_t launch_scale2(int64_t n, double ca, const double *a, double cb, const double *b, double *oa,
+                         double *ob, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_scale2, grid_for(n), dim3(256), 0, s, n, ca, a, cb, b, oa, ob);
+  return hipGetLastError();
+}
+
+hipError_t launch_dot(int64_t n, const double *a, const double *b, double *part, double *out,
+                      hipStream_t s) {
+  const int64_t nb = std::max<int64_t>(1, std::min<int64_t>(kDotBlocks, (n + 255) / 256));
+  hipLaunchKernelGGL(k_dot_partial, dim3((unsigned)nb), dim3(256), 0, s, n, a, b, part);
+  hipLaunchKernelGGL(k_reduce_sum, dim3(1), dim3(256), 0, s, nb, part, out);
   return hipGetLastError();
 }
 

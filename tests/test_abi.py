@@ -76,8 +76,10 @@ def test_struct_layouts_match_header(tmp_path):
         pytest.skip("gcc not available")
     inc = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "include")
     src = tmp_path / "layout.c"
-    fields = {"acse_problem": [f for f, _ in acse.Problem._fields_],
-              "acse_options": [f for f, _ in acse.Options._fields_]}
+    structs = (("acse_problem", acse.Problem), ("acse_options", acse.Options),
+               ("acse_profile_data", acse.ProfileData), ("acse_solve_options", acse.SolveOptions),
+               ("acse_trial", acse.Trial), ("acse_solve_result", acse.SolveResult))
+    fields = {st: [f for f, _ in cls._fields_] for st, cls in structs}
     lines = ["#include <stdio.h>", "#include <stddef.h>", "#include \"acse.h\"", "int main(void) {"]
     for st, fs in fields.items():
         lines.append(f'  printf("{st} %zu\\n", sizeof({st}));')
@@ -89,7 +91,7 @@ def test_struct_layouts_match_header(tmp_path):
     subprocess.run([gcc, "-std=c99", "-I", inc, str(src), "-o", str(exe)], check=True)
     out = dict(line.rsplit(" ", 1) for line in subprocess.run([str(exe)], check=True, capture_output=True,
                                                                text=True).stdout.split("\n") if line)
-    for st, cls in (("acse_problem", acse.Problem), ("acse_options", acse.Options)):
+    for st, cls in structs:
         assert int(out[st]) == ctypes.sizeof(cls), st
         for f, _ in cls._fields_:
             assert int(out[f"{st}.{f}"]) == getattr(cls, f).offset, (st, f)
