@@ -103,13 +103,15 @@ typedef struct {
   int32_t flags;          /* bitwise OR of ACSE_FLAG_* (0 = none) */
 } acse_options;
 
-/* acse_options.flags: run the general-size transform kernels at every r (the
- * one-index transforms for the ph A operands (otherwise r > 56); the G2 kernel
- * that stores G2, followed by two one-index transforms for the g G2 g product
- * (otherwise r > 52), without its mirrored-row staging (otherwise r > 81); the
- * row-chunked assembly (otherwise r > 81)).  Same results up to rounding
- * order; meant for verifying those kernels at small r.  Other bits are an
- * ACSE_ERR_ARG. */
+/* acse_options.flags: run the general-size kernels at every r (the one-index
+ * transforms for the ph A operands (otherwise r > 56); the G2 kernel that
+ * stores G2, followed by two one-index transforms for the g G2 g product
+ * (otherwise r > 52), without its mirrored-row staging (otherwise r > 82) and
+ * without its pair-index tables (otherwise r in 80..82 and r > 94); the
+ * row-chunked assembly (otherwise r > 81); the mode-product kernel in its
+ * r > 64 shape and the Gram kernel in its r > 80 shape).  Same results up to
+ * rounding order; meant for verifying those kernels at small r.  Other bits
+ * are an ACSE_ERR_ARG. */
 #define ACSE_FLAG_GENERAL_KERNELS 1
 
 /* acse_options.flags: before computing, check on the device that the inputs

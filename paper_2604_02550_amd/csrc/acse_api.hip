@@ -263,9 +263,10 @@ acse_status prep_rdm_operands(acse_ctx c, const acse_problem *p, GemmPrec prec, 
   return ACSE_OK;
 }
 
-ModeArgs mode_base(int r, const double *g) {
+ModeArgs mode_base(acse_ctx c, int r, const double *g) {
   ModeArgs m{};
   m.r = r;
+  m.wide = c->general ? 1 : 0;
   m.g = g;
   m.c1 = 1.0;
   m.c2 = 0.0;
@@ -295,11 +296,11 @@ acse_status map_front(acse_ctx c, const acse_problem *p, GemmPrec prec, const do
     } else {
       HIP_TRY(c, launch_f(r, Xaa, Xab, g, w.fpart, w.f, s));
     }
-    HIP_TRY(c, launch_t(r, w.Waa, Xaa, w.Wab, Xab, w.tpart, w.t, s));
+    HIP_TRY(c, launch_t(r, w.Waa, Xaa, w.Wab, Xab, w.tpart, w.t, s, c->general));
 
     // H[k,l,(r,s)] = sum_p X[k,p,(r,s)] g[p,l]
     for (int b = 0; b < 2; ++b) {
-      ModeArgs m = mode_base(r, g);
+      ModeArgs m = mode_base(c, r, g);
       m.A = r; m.Bn = r2; m.in1 = b ? Xab : Xaa; m.transpose_m = 1;
       m.so1 = r3; m.so0 = 0; m.sx = r2; m.sb = 1; m.out_cols_fast = 1;
       HIP_TRY(c, launch_mode(GEMM_F64, m, OperandRef{b ? w.Hab : w.Haa, nullptr}, s));
@@ -315,11 +316,11 @@ acse_status map_front(acse_ctx c, const acse_problem *p, GemmPrec prec, const do
                            operand(w, OP_BA, prec, r), s));
     }
     if (r > kG2cMaxR || c->general) for (int b = 0; b < 2; ++b) {
-      ModeArgs m1 = mode_base(r, g);  // T1[k,l,r,j] = sum_s g[j,s] G2[k,l,r,s]
+      ModeArgs m1 = mode_base(c, r, g);  // T1[k,l,r,j] = sum_s g[j,s] G2[k,l,r,s]
       m1.A = r3; m1.Bn = 1; m1.in1 = b ? w.G2ab : w.G2aa;
       m1.so1 = r; m1.so0 = 0; m1.sx = 1; m1.sb = 0; m1.out_cols_fast = 0;
       HIP_TRY(c, launch_mode(GEMM_F64, m1, OperandRef{w.T1, nullptr}, s));
-      ModeArgs m2 = mode_base(r, g);  // C^T[k,l,i,j] = 4/3 sum_r g[i,r] T1[k,l,r,j]
+      ModeArgs m2 = mode_base(c, r, g);  // C^T[k,l,i,j] = 4/3 sum_r g[i,r] T1[k,l,r,j]
       m2.A = r2; m2.Bn = r; m2.in1 = w.T1; m2.alpha = 4.0 / 3.0;
       m2.so1 = r2; m2.so0 = 0; m2.sx = r; m2.sb = 1; m2.out_cols_fast = 1;
       HIP_TRY(c, launch_mode(GEMM_F64, m2, OperandRef{b ? w.Cab : w.Caa, nullptr}, s));
@@ -329,13 +330,13 @@ acse_status map_front(acse_ctx c, const acse_problem *p, GemmPrec prec, const do
     for (int q : {OP_LP, OP_LM, OP_L3})
       HIP_TRY(c, launch_zero_kpad(prec, r, ld, operand(w, q, prec, r), s));
     for (int b = 0; b < 2; ++b) {
-      ModeArgs m = mode_base(r, g);
+      ModeArgs m = mode_base(c, r, g);
       m.A = r2; m.Bn = r; m.in1 = Xaa; m.in2 = Xab; m.c2 = b ? -1.0 : 1.0;
       m.adiv = r; m.so1 = (int64_t)r * ld; m.so0 = r; m.sx = ld; m.sb = 1; m.out_cols_fast = 1;
       HIP_TRY(c, launch_mode(prec, m, operand(w, b ? OP_LM : OP_LP, prec, r), s));
     }
     {  // L3[(k,j),(p,s)] = sum_r g[j,r] X_ab[k,p,s,r]
-      ModeArgs m = mode_base(r, g);
+      ModeArgs m = mode_base(c, r, g);
       m.A = r3; m.Bn = 1; m.in1 = Xab;
       m.adiv = r2; m.so1 = (int64_t)r * ld; m.so0 = 1; m.sx = ld; m.sb = 0; m.out_cols_fast = 1;
       HIP_TRY(c, launch_mode(prec, m, operand(w, OP_L3, prec, r), s));
@@ -804,7 +805,7 @@ extern "C" acse_status acse_residual_vjp(acse_ctx ctx, const acse_problem *prob,
   auto mode = [&](const double *in1, const double *in2, double c2, const double *M, int tr,
                   int64_t A, int64_t Bn, double alpha, double *out, int64_t adiv, int64_t so1,
                   int64_t so0, int64_t sx, int64_t sb, int cols_fast, int acc) -> hipError_t {
-    ModeArgs m = mode_base(r, M);
+    ModeArgs m = mode_base(ctx, r, M);
     m.A = A; m.Bn = Bn; m.in1 = in1; m.in2 = in2; m.c2 = c2; m.transpose_m = tr;
     m.alpha = alpha; m.adiv = adiv; m.so1 = so1; m.so0 = so0; m.sx = sx; m.sb = sb;
     m.out_cols_fast = cols_fast; m.accumulate = acc;
@@ -825,7 +826,7 @@ extern "C" acse_status acse_residual_vjp(acse_ctx ctx, const acse_problem *prob,
   if ((st = prep_rdm_operands(ctx, prob, prec)) != ACSE_OK) return st;
   HIP_TRY(ctx, launch_fold(r, N, prob->h, prob->V, w.Aaa, w.Aab, s));
   HIP_TRY(ctx, launch_f(r, w.Aaa, w.Aab, g, w.fpart, w.f, s));
-  HIP_TRY(ctx, launch_t(r, w.Waa, w.Aaa, w.Wab, w.Aab, w.tpart, w.t, s));
+  HIP_TRY(ctx, launch_t(r, w.Waa, w.Aaa, w.Wab, w.Aab, w.tpart, w.t, s, ctx->general));
   for (int b = 0; b < 2; ++b)
     HIP_TRY(ctx, mode(b ? w.Aab : w.Aaa, nullptr, 0.0, g, 1, r, r2, 1.0, b ? w.Hab : w.Haa, 1, r3, 0,
                       r2, 1, 1, 0));
@@ -886,7 +887,7 @@ extern "C" acse_status acse_residual_vjp(acse_ctx ctx, const acse_problem *prob,
                    int64_t adiv, int64_t so1, int64_t so0, int64_t sb) -> hipError_t {
       hipError_t e = launch_zero_kpad(prec, r, ld, vop(q), s);
       if (e != hipSuccess) return e;
-      ModeArgs m = mode_base(r, g);
+      ModeArgs m = mode_base(ctx, r, g);
       m.A = A; m.Bn = Bn; m.in1 = in1; m.in2 = in2; m.c2 = c2;
       m.adiv = adiv; m.so1 = so1; m.so0 = so0; m.sx = 1; m.sb = sb; m.out_cols_fast = 1;
       return launch_mode(prec, m, vop(q), s);
@@ -984,7 +985,7 @@ extern "C" acse_status acse_residual_vjp(acse_ctx ctx, const acse_problem *prob,
     HIP_TRY(ctx, permute(GEMM_F64, natref(T2), false, Hbaa, lead1, 1.0, nullptr, ID, 0.0, 0));
     HIP_TRY(ctx, permute(GEMM_F64, natref(T3), false, w.Aab, lead1, 1.0, nullptr, ID, 0.0, 0));
     HIP_TRY(ctx, permute(GEMM_F64, natref(T4), false, Hbab, lead1, 1.0, nullptr, ID, 0.0, 0));
-    HIP_TRY(ctx, launch_gram(r, T1, T2, 1.0, T3, T4, 1.0, w.tpart, gb, 1, s));
+    HIP_TRY(ctx, launch_gram(r, T1, T2, 1.0, T3, T4, 1.0, w.tpart, gb, 1, s, ctx->general));
   }
   // W-bar from the ph B operands
   {
@@ -1019,12 +1020,12 @@ extern "C" acse_status acse_residual_vjp(acse_ctx ctx, const acse_problem *prob,
     HIP_TRY(ctx, permute(GEMM_F64, natref(T2), false, w.Aaa, r_kps, 1.0, w.Aab, r_kps, 1.0, 0));
     HIP_TRY(ctx, permute(GEMM_F64, natref(T3), false, Lmb, i_kps, 1.0, nullptr, ID, 0.0, 0));
     HIP_TRY(ctx, permute(GEMM_F64, natref(T4), false, w.Aaa, r_kps, 1.0, w.Aab, r_kps, -1.0, 0));
-    HIP_TRY(ctx, launch_gram(r, T1, T2, 1.0, T3, T4, 1.0, w.tpart, gb, 1, s));
+    HIP_TRY(ctx, launch_gram(r, T1, T2, 1.0, T3, T4, 1.0, w.tpart, gb, 1, s, ctx->general));
     // gamma-bar[j,r] += sum L3b[k,j,p,s] A_ab[k,p,s,r]
     const int r_kps3[4] = {3, 0, 1, 2};  // [r][k,p,s] from A_ab[k,p,s,r]
     HIP_TRY(ctx, permute(GEMM_F64, natref(T1), false, L3b, i_kps, 1.0, nullptr, ID, 0.0, 0));
     HIP_TRY(ctx, permute(GEMM_F64, natref(T2), false, w.Aab, r_kps3, 1.0, nullptr, ID, 0.0, 0));
-    HIP_TRY(ctx, launch_gram(r, T1, T2, 1.0, nullptr, nullptr, 0.0, w.tpart, gb, 1, s));
+    HIP_TRY(ctx, launch_gram(r, T1, T2, 1.0, nullptr, nullptr, 0.0, w.tpart, gb, 1, s, ctx->general));
   }
   // W = Gamma2 - 2/3 g^g:  gamma-bar from W-bar
   HIP_TRY(ctx, contract({term(Wbaa, 0, 2, 1, 3, g, -2.0 / 3.0), term(Wbaa, 1, 3, 0, 2, g, -2.0 / 3.0),

@@ -23,9 +23,10 @@ struct ModeArgs {
   int64_t adiv, so1, so0, sx, sb;
   int out_cols_fast;  // output contiguous along (a,b) columns rather than along x
   int accumulate;     // FP64 output only: out += result
+  int wide;           // take the kernel shape of r > 64 (16-column panels, two
+                      // row blocks per wave, K padded to 80 or 96) at any r
 };
 constexpr int kModeMaxR = 96;
-size_t mode_lds_bytes(int r);
 
 hipError_t launch_fold(int r, int N, const double *h, const double *V, double *Aaa, double *Aab,
                        hipStream_t s);
@@ -105,14 +106,15 @@ hipError_t launch_finish(int r, double sigma, const double *Saa, const double *S
 int64_t finish_partials(int r);
 hipError_t launch_t_reduce(int r, int nparts, const double *part, double *t, hipStream_t s,
                            int accumulate = 0);
-// out[x,y] (+)= sum_z (w1 P1[x,z] Q1[y,z] + w2 P2[x,z] Q2[y,z]),  z in [0, r^3), P*,Q* natural [r][r^3]
+// out[x,y] (+)= sum_z (w1 P1[x,z] Q1[y,z] + w2 P2[x,z] Q2[y,z]),  z in [0, r^3), P*,Q* natural [r][r^3].
+// wide: use the kernel shape of the largest r (six 16-row blocks per side) at any r.
 hipError_t launch_gram(int r, const double *P1, const double *Q1, double w1, const double *P2,
                        const double *Q2, double w2, double *part, double *out, int accumulate,
-                       hipStream_t s);
+                       hipStream_t s, bool wide = false);
 int t_partial_blocks();
 // t[j,k] = sum_{prs} (W_aa[j,p,r,s] A_aa[k,p,r,s] + 2 W_ab[j,p,r,s] A_ab[k,p,r,s])
 hipError_t launch_t(int r, const double *Waa, const double *Aaa, const double *Wab,
-                    const double *Aab, double *part, double *t, hipStream_t s);
+                    const double *Aab, double *part, double *t, hipStream_t s, bool wide = false);
 hipError_t launch_energy(int r, int N, const double *h, const double *V, const double *d2aa,
                          const double *d2ab, double *partial, double *E_out, hipStream_t s);
 // 2D <- (2D + eps U) rescaled to the input trace per block (in place), the

@@ -1724,18 +1724,12 @@ hipError_t launch_f(int r, const double *Aaa, const double *Aab, const double *g
 // r <= 64: one 16-row block of M per wave, 32-column panels; r <= 96: two
 // row blocks per wave, 16-column panels (the prefetch stays at 8 per thread).
 // K steps: exact for r <= 64; rounded up to a multiple of 4 above.
-static int mode_cols(int r) { return r <= 64 ? 32 : 16; }
-static int mode_ks(int r) { return r <= 64 ? (r + 3) / 4 : ((((r + 3) / 4) + 3) / 4 * 4); }
-
-size_t mode_lds_bytes(int r) {
-  const int ldt = mode_cols(r) + 1;
-  return (size_t)(2 * 4 * mode_ks(r) * ldt) * sizeof(double);
-}
-
+// (The wide shape is also selectable at small r, to verify it there.)
 template <class O, int COLS, int NRB, bool HAS2, int KS>
 static hipError_t launch_mode_t(const ModeArgs &m, O out, hipStream_t s) {
   static int resident[kModeMaxR + 1] = {};  // blocks the device holds at once, by r
-  const size_t lds = mode_lds_bytes(m.r);
+  static_assert((size_t)COLS * 4 * KS <= (size_t)ModeShape<COLS>::PF * 256, "panel must fit the prefetch");
+  const size_t lds = (size_t)2 * 4 * KS * (COLS + 1) * sizeof(double);  // two panels
   int &res = resident[m.r];
   if (res == 0) {
     const void *fn = reinterpret_cast<const void *>(&k_mode<O, COLS, NRB, HAS2, KS>);
@@ -1756,15 +1750,16 @@ static hipError_t launch_mode_t(const ModeArgs &m, O out, hipStream_t s) {
 
 template <class O, bool HAS2>
 static hipError_t launch_mode_h(const ModeArgs &m, O out, hipStream_t s) {
-  switch (mode_ks(m.r)) {
+  if (m.wide || m.r > 64)
+    return m.r <= 80 ? launch_mode_t<O, 16, 2, HAS2, 20>(m, out, s) : launch_mode_t<O, 16, 2, HAS2, 24>(m, out, s);
+  switch ((m.r + 3) / 4) {
 #define ACSE_MODE_KS(K) \
     case K: return launch_mode_t<O, 32, 1, HAS2, K>(m, out, s);
     ACSE_MODE_KS(1) ACSE_MODE_KS(2) ACSE_MODE_KS(3) ACSE_MODE_KS(4) ACSE_MODE_KS(5) ACSE_MODE_KS(6)
     ACSE_MODE_KS(7) ACSE_MODE_KS(8) ACSE_MODE_KS(9) ACSE_MODE_KS(10) ACSE_MODE_KS(11)
     ACSE_MODE_KS(12) ACSE_MODE_KS(13) ACSE_MODE_KS(14) ACSE_MODE_KS(15) ACSE_MODE_KS(16)
 #undef ACSE_MODE_KS
-    case 20: return launch_mode_t<O, 16, 2, HAS2, 20>(m, out, s);
-    default: return launch_mode_t<O, 16, 2, HAS2, 24>(m, out, s);
+    default: return hipErrorInvalidValue;
   }
 }
 
@@ -1789,7 +1784,7 @@ hipError_t launch_g2(GemmPrec prec, int r, bool general, const double *Aaa, cons
   const size_t lds2 = (size_t)2 * r * (r + 1) * sizeof(double);
   const size_t lds3 = lds2 + (size_t)r * (r + 1) * sizeof(double);
   const bool mir = !general && lds3 <= kMaxLds;
-  const int tables = (mir ? lds3 : lds2) + pair_table_bytes(r) <= kMaxLds;
+  const int tables = !general && (mir ? lds3 : lds2) + pair_table_bytes(r) <= kMaxLds;
   const size_t lds = (mir ? lds3 : lds2) + (tables ? pair_table_bytes(r) : 0);
   const int ld_lt = (int)ld_pair_lt(r), ld_le = (int)ld_pair_le(r);
   auto go = [&](auto kern, auto tag) -> hipError_t {
@@ -1922,10 +1917,10 @@ static hipError_t launch_gram_nb(int r, const double *P1, const double *Q1, doub
 
 hipError_t launch_gram(int r, const double *P1, const double *Q1, double w1, const double *P2,
                        const double *Q2, double w2, double *part, double *out, int accumulate,
-                       hipStream_t s) {
+                       hipStream_t s, bool wide) {
   if (!P2) { Q2 = nullptr; w2 = 0.0; }
   hipError_t err;
-  switch ((r + 15) / 16) {
+  switch (wide ? 6 : (r + 15) / 16) {
     case 1: err = launch_gram_nb<1>(r, P1, Q1, w1, P2, Q2, w2, part, s); break;
     case 2: err = launch_gram_nb<2>(r, P1, Q1, w1, P2, Q2, w2, part, s); break;
     case 3: err = launch_gram_nb<3>(r, P1, Q1, w1, P2, Q2, w2, part, s); break;
@@ -1938,8 +1933,8 @@ hipError_t launch_gram(int r, const double *P1, const double *Q1, double w1, con
 }
 
 hipError_t launch_t(int r, const double *Waa, const double *Aaa, const double *Wab,
-                    const double *Aab, double *part, double *t, hipStream_t s) {
-  return launch_gram(r, Waa, Aaa, 1.0, Wab, Aab, 2.0, part, t, 0, s);
+                    const double *Aab, double *part, double *t, hipStream_t s, bool wide) {
+  return launch_gram(r, Waa, Aaa, 1.0, Wab, Aab, 2.0, part, t, 0, s, wide);
 }
 
 

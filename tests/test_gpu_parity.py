@@ -104,12 +104,13 @@ def test_step_fp64(ctx, name, active):
 
 @pytest.mark.parametrize("name", ["tiny_fci", "r6", "r13"])
 def test_general_kernels_fp64(acse, ctx, name):
-    """The general-size transform kernels, which otherwise run only for r above the
-    limits of the faster ones (one-index transforms for the ph A operands (r > 56);
-    the G2 kernel that stores G2 plus two one-index transforms for g G2 g (r > 52),
-    without mirrored-row staging (r > 81); the row-chunked assembly (r > 81)),
-    selected at small r by ACSE_FLAG_GENERAL_KERNELS: residual and a full step
-    against the oracle."""
+    """The general-size kernels, which otherwise run only for r above the limits
+    of the faster ones (one-index transforms for the ph A operands (r > 56); the
+    G2 kernel that stores G2 plus two one-index transforms for g G2 g (r > 52),
+    without mirrored-row staging (r > 82) or pair-index tables; the row-chunked
+    assembly (r > 81); the mode-product and Gram kernels in their large-r
+    shapes), selected at small r by ACSE_FLAG_GENERAL_KERNELS: residual and a
+    full step against the oracle."""
     p = PROBLEMS[name]()
     print(f"[general_kernels_fp64] {name} r={p['r']}", flush=True)
     raa, rab, n2 = ost.residual(p["h"], p["V"], p["N"], p["gamma"], p["d2aa"], p["d2ab"])
@@ -125,6 +126,21 @@ def test_general_kernels_fp64(acse, ctx, name):
         assert rel(cpu(g[key]), o[key]) < TOL64, key
         assert maxrel(cpu(g[key]), o[key]) < TOL64, key
     assert abs(g["energy"] - o["energy"]) <= TOL64 * max(1.0, abs(o["energy"]))
+
+
+@pytest.mark.parametrize("precision,tol", [("fp32", 1e-5), ("bf16x3", 5e-5)])
+def test_general_kernels_mixed(acse, ctx, precision, tol):
+    """The general-size kernels with FP32 / split-BF16 operand writers: against
+    the default kernels in the same precision (the FP64 transforms differ only
+    in summation order, so the operands differ by at most an ulp or two)."""
+    p = PROBLEMS["r13"]()
+    print(f"[general_kernels_mixed] r13 {precision}", flush=True)
+    a = ctx.step(p["h"], p["V"], p["gamma"], p["d2aa"], p["d2ab"], p["N"] // 2, eps=1e-3,
+                 precision=precision, return_ru=True)
+    b = ctx.step(p["h"], p["V"], p["gamma"], p["d2aa"], p["d2ab"], p["N"] // 2, eps=1e-3,
+                 precision=precision, return_ru=True, flags=acse.FLAG_GENERAL_KERNELS)
+    for key in ("R_aa", "R_ab", "U_aa", "U_ab"):
+        assert rel(cpu(b[key]), cpu(a[key])) < tol, key
 
 
 def test_unknown_option_flags_rejected(acse, ctx):
