@@ -151,6 +151,32 @@ def test_unknown_option_flags_rejected(acse, ctx):
         ctx.residual_raw(prob, ctx.options("fp64", flags=4), out[0], out[1])
 
 
+@pytest.mark.parametrize("r,N,active", [(2, 2, None), (3, 2, None), (3, 6, None), (5, 10, None),
+                                         (2, 4, None), (6, 4, "all"), (6, 4, "none")])
+def test_edge_sizes_fp64(ctx, r, N, active):
+    """Degenerate sizes: the smallest r, one electron pair (1/(N-1) = 1), every
+    orbital doubly occupied (N = 2r), and the active mask with every orbital
+    active (R_m = 0, so U = 0 and the step leaves E) or none active."""
+    p = gen.problem(r, N, 2 * r, seed=40 + r + N)
+    act = None if active is None else np.full(r, active == "all")
+    print(f"[edge_sizes_fp64] r={r} N={N} active={active}", flush=True)
+    o = ost.step(p["h"], p["V"], p["N"], p["gamma"], p["d2aa"], p["d2ab"], 1e-3, active=act)
+    g = ctx.step(p["h"], p["V"], p["gamma"], p["d2aa"], p["d2ab"], N // 2, eps=1e-3, active=act,
+                 return_ru=True)
+    # errors relative to the larger block of each pair (at r = 2 the alpha-alpha
+    # residual is zero up to rounding: one pair, antisymmetric under the exchange)
+    for pair in (("R_aa", "R_ab"), ("U_aa", "U_ab"), ("d2aa", "d2ab")):
+        scale = max(np.abs(o[k]).max() for k in pair)
+        for key in pair:
+            assert np.abs(cpu(g[key]) - o[key]).max() <= TOL64 * scale, key
+    assert abs(g["energy"] - o["energy"]) <= TOL64 * max(1.0, abs(o["energy"]))
+    assert abs(g["norm2"] - o["norm2"]) <= TOL64 * max(o["norm2"], 1e-300)
+    if active == "all":
+        assert float(g["U_aa"].abs().max()) == 0.0 and float(g["U_ab"].abs().max()) == 0.0
+        e0 = ctx.energy(p["h"], p["V"], p["d2aa"], p["d2ab"], N // 2)
+        assert abs(g["energy"] - e0) <= 1e-12 * max(1.0, abs(e0))
+
+
 def test_update_map_fp64(ctx):
     p = PROBLEMS["r10"]()
     o = ost.step(p["h"], p["V"], p["N"], p["gamma"], p["d2aa"], p["d2ab"], 1e-3)
