@@ -345,32 +345,43 @@ acse_status map_front(acse_ctx c, const acse_problem *p, GemmPrec prec, const do
   return ACSE_OK;
 }
 
+// K extent a product runs over: the operand buffers are zero from K to their
+// row stride ld (a multiple of 64, the largest K tile of any precision), so a
+// precision whose tile configurations all take smaller K tiles (FP64: 16)
+// stops at the next multiple of its largest one instead of running over up to
+// 63 columns of zeros.
+int gemm_kp(GemmPrec prec, int K, int ld) {
+  int bk = 1;
+  for (int c = 0; c < gemm_num_tiles(prec); ++c) bk = std::max(bk, gemm_tile_info(prec, c).bk);
+  return (int)std::min<int64_t>(ld, round_up(K, bk));
+}
+
 // The six pair-index products of F(X) as GEMM descriptors: three packed pp
 // products (Z_aa over pairs i<j and K r<s; the alpha-beta block split into its
 // parts symmetric (i<=j, r<=s) and antisymmetric (i<j, r<s) under the pair
 // exchange) and the three ph products.
 void map_probs(const Workspace &w, GemmPrec prec, int r, GemmProb *out) {
   const int64_t r2 = (int64_t)r * r, r3 = r2 * r;
-  auto set = [&](int q, int ia, int ib, double alpha, double *C, int M, int ld, int64_t sm1,
+  auto set = [&](int q, int ia, int ib, double alpha, double *C, int M, int K, int ld, int64_t sm1,
                  int64_t sm0, int64_t sn1, int64_t sn0) {
     GemmProb &P = out[q];
     P = GemmProb{};
     OperandRef a = operand(w, ia, prec, r), bb = operand(w, ib, prec, r);
     P.A = a.hi; P.A2 = a.lo; P.B = bb.hi; P.B2 = bb.lo;
     P.C = C; P.alpha = alpha;
-    P.M = M; P.N = (int)r2; P.Kp = ld; P.ld = ld; P.rdiv = r;
+    P.M = M; P.N = (int)r2; P.Kp = gemm_kp(prec, K, ld); P.ld = ld; P.rdiv = r;
     P.sm1 = sm1; P.sm0 = sm0; P.sn1 = sn1; P.sn0 = sn0;
-    P.ksplit = 1; P.kchunk = ld; P.accumulate = 0;
+    P.ksplit = 1; P.kchunk = P.Kp; P.accumulate = 0;
   };
   const int nlt = npair_lt(r), nle = npair_le(r);
   const int ldlt = (int)ld_pair_lt(r), ldle = (int)ld_pair_le(r), ld = (int)op_ld(r);
   // packed rows p -> C + p r^2 + (k r + l)
-  set(0, OP_DAA, OP_BAA, 2.0, w.Zaa, nlt, ldlt, r3, r2, r, 1);
-  set(1, OP_DS, OP_BS, 4.0, w.Zab, nle, ldle, r3, r2, r, 1);
-  set(2, OP_DA, OP_BA, 4.0, w.Zab + (int64_t)nle * r2, nlt, ldlt, r3, r2, r, 1);
-  set(3, OP_LP, OP_RP, 1.0, w.Pp, (int)r2, ld, r, r3, r2, 1);    // rows (k,i), cols (j,l) -> [i,j,k,l]
-  set(4, OP_LM, OP_RM, 1.0, w.Pm, (int)r2, ld, r, r3, r2, 1);
-  set(5, OP_L3, OP_R3, -2.0, w.E3, (int)r2, ld, r, r2, r3, 1);   // rows (k,j), cols (i,l) -> [i,j,k,l]
+  set(0, OP_DAA, OP_BAA, 2.0, w.Zaa, nlt, nlt, ldlt, r3, r2, r, 1);
+  set(1, OP_DS, OP_BS, 4.0, w.Zab, nle, nle, ldle, r3, r2, r, 1);
+  set(2, OP_DA, OP_BA, 4.0, w.Zab + (int64_t)nle * r2, nlt, nlt, ldlt, r3, r2, r, 1);
+  set(3, OP_LP, OP_RP, 1.0, w.Pp, (int)r2, (int)r2, ld, r, r3, r2, 1);    // rows (k,i), cols (j,l) -> [i,j,k,l]
+  set(4, OP_LM, OP_RM, 1.0, w.Pm, (int)r2, (int)r2, ld, r, r3, r2, 1);
+  set(5, OP_L3, OP_R3, -2.0, w.E3, (int)r2, (int)r2, ld, r, r2, r3, 1);   // rows (k,j), cols (i,l) -> [i,j,k,l]
 }
 
 // Stage 4 of F(X): assembly, (ij) <-> (kl) exchange, mask and the FP64 norm
@@ -865,10 +876,10 @@ extern "C" acse_status acse_residual_vjp(acse_ctx ctx, const acse_problem *prob,
     OperandRef a = vop(ia), bb = vop(ib);
     P.A = a.hi; P.A2 = a.lo; P.B = bb.hi; P.B2 = bb.lo;
     P.C = C; P.alpha = alpha;
-    P.M = (int)r2; P.N = (int)r2; P.Kp = ld; P.ld = ld; P.rdiv = r;
+    P.M = (int)r2; P.N = (int)r2; P.Kp = gemm_kp(prec, (int)r2, ld); P.ld = ld; P.rdiv = r;
     // output (m/r, m%r, n/r, n%r) -> natural positions om[0..3] of the result
     P.sm1 = nat.S[om[0]]; P.sm0 = nat.S[om[1]]; P.sn1 = nat.S[om[2]]; P.sn0 = nat.S[om[3]];
-    P.ksplit = 1; P.kchunk = ld; P.accumulate = 0;
+    P.ksplit = 1; P.kchunk = P.Kp; P.accumulate = 0;
   };
   int use_cfg = opts ? opts->tile : -1;
   if (use_cfg < 0) {
