@@ -31,7 +31,8 @@ sys.path.insert(0, ROOT)
 PEAK_TFLOPS = {"fp64": 78.6, "fp32": 157.3, "bf16x3": 2516.6}
 GOLDEN = os.path.join(ROOT, "tests", "golden", "r50_step.json")
 TRAFFIC = os.path.join(ROOT, "profiles", "gemm_traffic_r50.json")
-GEMM_SRC = os.path.join(ROOT, "paper_2604_02550_amd", "csrc", "gemm.hip")
+# the GEMM kernel and the host code that sets up its launches (operand layout, K extent)
+TRAFFIC_SRCS = [os.path.join(ROOT, "paper_2604_02550_amd", "csrc", f) for f in ("gemm.hip", "acse_api.hip")]
 
 
 def gemm_flops(r):
@@ -211,8 +212,11 @@ def bench_solve(acse, ctx, prob, work, pristine, torch, controls, iters, eps, st
 
 
 def src_hash():
-    with open(GEMM_SRC, "rb") as f:
-        return hashlib.sha256(f.read()).hexdigest()[:16]
+    h = hashlib.sha256()
+    for path in TRAFFIC_SRCS:
+        with open(path, "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
 
 
 def main():
@@ -330,7 +334,7 @@ def main():
     if os.path.exists(TRAFFIC):
         t = json.load(open(TRAFFIC))
         k = t.get("kernels", {}).get(gemm_kernel_name(head, hr["tile_config"]))
-        if t.get("gemm_src_sha256_16") == src_hash() and k is not None:
+        if t.get("src_sha256_16") == src_hash() and k is not None:
             traffic = k.get("bytes_per_launch")
     line = {
         "metric": "ACSE residual evals/s + TFLOP/s at r=50: FP64 vs mixed at |dE|<1e-7 Eh",
