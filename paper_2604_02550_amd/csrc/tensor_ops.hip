@@ -751,76 +751,76 @@ k_g2(int r, int ld_lt, int ld_le, const double *__restrict__ Aaa, const double *
 
 // ---------------------------------------------------------------------------
 // G2 fused with C^T = alpha g G2 g (r <= 52): the G2 rows never leave LDS.
-// Persistent blocks of 8 waves walk the rows (k,l).  Per row: the mirrored
-// H_ab row is staged; G2_aa, G2_ab (zero-padded r x r matrices, row stride
-// 4 KS + 2) and B = A - G2 go to LDS; the packed pp B operands are written;
-// then waves 0-3 (alpha-alpha) and 4-7 (alpha-beta) form U^T = g G2^T and
-// C = alpha g U on the FP64 MFMA, with g (symmetric) as the A operand held in
-// registers (wave w: rows 16 (w mod 4)..) and the B operands read transposed
-// from LDS (conflict-free for a row stride = 2 mod 4).  The next row's inputs
-// are loaded into registers while the MFMAs run.
+// Persistent blocks of 4 waves walk the items (row (k,l), side), side 0 the
+// alpha-alpha block and side 1 the alpha-beta block: an item reads three input
+// rows (the natural and the mirrored H row, the A row), and a block needs the
+// LDS of one side only, so two blocks share a CU and one block's loads and
+// stores proceed while the other runs its MFMAs.  Per item: the mirrored H_ab
+// row is staged (alpha-beta only); G2 of the side (a zero-padded r x r matrix,
+// row stride 4 KS + 2) and B = A - G2 go to LDS; the side's packed pp B
+// operand rows are written; then U^T = g G2^T and C = alpha g U on the FP64
+// MFMA, with g (symmetric) as the A operand held in registers (wave w: rows
+// 16 w ..) and the B operands read transposed from LDS (conflict-free for a
+// row stride = 2 mod 4).
 // ---------------------------------------------------------------------------
 template <class O, int KS>
-__global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(2)))
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2)))
 k_g2c(int r, int ld_lt, int ld_le, const double *__restrict__ Aaa, const double *__restrict__ Aab,
       const double *__restrict__ Haa, const double *__restrict__ Hab, const double *__restrict__ f,
       const double *__restrict__ g, double alpha, double *__restrict__ Caa, double *__restrict__ Cab,
-      O Baa, O BS, O BA, int nrow) {
-  constexpr int NT = 512;
+      O Baa, O BS, O BA, int nitem) {
+  constexpr int NT = 256;
   constexpr int NB = (4 * KS + 15) / 16, NR = 16 * NB, RP = 4 * KS + 2;
+  static_assert(NB <= 4, "one 16-row block of U per wave");
   constexpr int PF = (4 * KS * 4 * KS + NT - 1) / NT;  // elements of one row per thread (r <= 4 KS)
   extern __shared__ double g2c_smem[];
-  double *const G = g2c_smem;                 // [2][NR][RP]: G2_aa, G2_ab
-  double *const Z = g2c_smem + 2 * NR * RP;   // B_aa, B_ab, mirrored H_ab ([r][RP] each), later [2][NR][RP] U^T
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int lr = lane & 15, lk = lane >> 4;
-  const int blk = wave & 3, side = wave >> 2;
   const int r2 = r * r;
-  double *const Ba = Z, *const Bb = Z + r * RP, *const MH = Z + 2 * r * RP;
-  // rows k and l of f for the current row, then the pair tables (after the Z region)
-  double *const FK = Z + (3 * r * RP > 2 * NR * RP ? 3 * r * RP : 2 * NR * RP), *const FL = FK + r;
+  const int zlen = 2 * r * RP > NR * RP ? 2 * r * RP : NR * RP;
+  double *const G = g2c_smem;       // [NR][RP] G2 of the item's side
+  double *const Z = G + NR * RP;    // B and the mirrored H_ab row ([r][RP] each), later U^T [NR][RP]
+  double *const Bs = Z, *const MH = Z + r * RP;
+  double *const FK = Z + zlen, *const FL = FK + r;  // rows k and l of f
   uint16_t *const tle = reinterpret_cast<uint16_t *>(FL + r), *const tlt = tle + npair_le(r);
   pair_tables(r, tle, tlt, tid, NT);
   double afr[KS];
 #pragma unroll
   for (int ks = 0; ks < KS; ++ks) {
-    const int x = blk * 16 + lr, y = ks * 4 + lk;
+    const int x = wave * 16 + lr, y = ks * 4 + lk;
     const bool ok = x < r && y < r;
     const double v = ld_ok(g, (int64_t)x * r + y, ok);
     afr[ks] = ok ? v : 0.0;
   }
-  for (int e = tid; e < 2 * NR * RP; e += NT) G[e] = 0.0;
-  double vhn[PF], vhm[PF], vbn[PF], vbm[PF], van[PF], vab[PF];
-  auto fetch = [&](int rw) {
-    const int kk = rw / r, ll = rw - (rw / r) * r;
-    const int64_t nat0 = (int64_t)rw * r2, mir0 = ((int64_t)ll * r + kk) * r2;
+  for (int e = tid; e < NR * RP; e += NT) G[e] = 0.0;
+  const int nlt = npair_lt(r), nle = npair_le(r);
+  __syncthreads();  // zero fill of G complete
+  for (int item = blockIdx.x; item < nitem; item += gridDim.x) {
+    const int row = item >> 1, side = item & 1;
+    const int k = row / r, l = row - (row / r) * r;
+    const int64_t nat0 = (int64_t)row * r2, mir0 = ((int64_t)l * r + k) * r2;
+    const double *H = side ? Hab : Haa, *A = side ? Aab : Aaa;
+    double vn[PF], vm[PF], va[PF];
 #pragma unroll
     for (int u = 0; u < PF; ++u) {
       const int e = tid + u * NT;
       const bool ok = e < r2;
-      vhn[u] = ld_ok(Haa, nat0 + e, ok);
-      vhm[u] = ld_ok(Haa, mir0 + e, ok);
-      vbn[u] = ld_ok(Hab, nat0 + e, ok);
-      vbm[u] = ld_ok(Hab, mir0 + e, ok);
-      van[u] = ld_ok(Aaa, nat0 + e, ok);
-      vab[u] = ld_ok(Aab, nat0 + e, ok);
+      vn[u] = ld_ok(H, nat0 + e, ok);
+      vm[u] = ld_ok(H, mir0 + e, ok);
+      va[u] = ld_ok(A, nat0 + e, ok);
     }
-  };
-  int row = blockIdx.x;
-  fetch(row);
-  __syncthreads();  // zero fill of G complete
-  for (;;) {
-    const int k = row / r, l = row - (row / r) * r;
+    if (side) {
 #pragma unroll
-    for (int u = 0; u < PF; ++u) {
-      const int e = tid + u * NT;
-      if (e < r2) {
-        const int x = e / r, y = e - (e / r) * r;
-        MH[x * RP + y] = vbm[u];
+      for (int u = 0; u < PF; ++u) {
+        const int e = tid + u * NT;
+        if (e < r2) {
+          const int x = e / r, y = e - (e / r) * r;
+          MH[x * RP + y] = vm[u];
+        }
       }
     }
     if (tid < r) FK[tid] = f[k * r + tid];
-    else if (tid - 256 >= 0 && tid - 256 < r) FL[tid - 256] = f[l * r + tid - 256];
+    else if (tid >= 128 && tid - 128 < r) FL[tid - 128] = f[l * r + tid - 128];
     __syncthreads();
 #pragma unroll
     for (int u = 0; u < PF; ++u) {
@@ -828,25 +828,40 @@ k_g2c(int r, int ld_lt, int ld_le, const double *__restrict__ Aaa, const double 
       if (e < r2) {
         const int rr = e / r, s = e - (e / r) * r;
         double gaa, gab;
-        g2_element(k, l, rr, s, vhn[u], vhm[u], vbn[u], MH[s * RP + rr], FK, FL, gaa, gab);
-        G[rr * RP + s] = gaa;
-        G[NR * RP + rr * RP + s] = gab;
-        Ba[rr * RP + s] = van[u] - gaa;
-        Bb[rr * RP + s] = vab[u] - gab;
+        if (side)
+          g2_element(k, l, rr, s, 0.0, 0.0, vn[u], MH[s * RP + rr], FK, FL, gaa, gab);
+        else
+          g2_element(k, l, rr, s, vn[u], vm[u], 0.0, 0.0, FK, FL, gaa, gab);
+        const double v = side ? gab : gaa;
+        G[rr * RP + s] = v;
+        Bs[rr * RP + s] = va[u] - v;
       }
     }
     __syncthreads();
-    g2_pack(r, (int64_t)row, ld_lt, ld_le, Ba, Bb, RP, tle, tlt, Baa, BS, BA, tid, NT);
-    const int next = row + (int)gridDim.x;
-    const bool more = next < nrow;
+    // packed pp B operand rows of the side (K padding included)
+    if (side) {
+      for (int q = tid; q < ld_le; q += NT) {
+        double v = 0.0;
+        if (q < nle) {
+          const int a = tle[q] >> 8, b = tle[q] & 255;
+          v = Bs[a * RP + b] + Bs[b * RP + a];
+        }
+        BS.put((int64_t)row * ld_le + q, v);
+      }
+    }
+    for (int q = tid; q < ld_lt; q += NT) {
+      double v = 0.0;
+      if (q < nlt) {
+        const int a = tlt[q] >> 8, b = tlt[q] & 255;
+        v = Bs[a * RP + b] - Bs[b * RP + a];
+      }
+      (side ? BA : Baa).put((int64_t)row * ld_lt + q, v);
+    }
     __syncthreads();  // B and the mirrored row are read; U^T may overwrite them
-    if (more) fetch(next);
-    const double *Gs = G + side * NR * RP;
-    double *Us = Z + side * NR * RP;
     mode_d4 acc[NB];
-    if (blk < NB) {
+    if (wave < NB) {
       // U^T[j][r'] = sum_s g[j][s] G2[r'][s]; accumulator item v of lane l:
-      // row j = 16 blk + l/16 + 4v, column r' = 16 cb + l%16
+      // row j = 16 wave + l/16 + 4v, column r' = 16 cb + l%16
 #pragma unroll
       for (int cb = 0; cb < NB; ++cb) acc[cb] = mode_d4{0.0, 0.0, 0.0, 0.0};
 #pragma unroll
@@ -854,17 +869,17 @@ k_g2c(int r, int ld_lt, int ld_le, const double *__restrict__ Aaa, const double 
         const int kr = ks * 4 + lk;
 #pragma unroll
         for (int cb = 0; cb < NB; ++cb)
-          acc[cb] = __builtin_amdgcn_mfma_f64_16x16x4f64(afr[ks], Gs[(cb * 16 + lr) * RP + kr], acc[cb], 0, 0, 0);
+          acc[cb] = __builtin_amdgcn_mfma_f64_16x16x4f64(afr[ks], G[(cb * 16 + lr) * RP + kr], acc[cb], 0, 0, 0);
       }
 #pragma unroll
       for (int cb = 0; cb < NB; ++cb)
         if (cb * 16 + lr < 4 * KS) {
 #pragma unroll
-          for (int v = 0; v < 4; ++v) Us[(blk * 16 + lk + 4 * v) * RP + cb * 16 + lr] = acc[cb][v];
+          for (int v = 0; v < 4; ++v) Z[(wave * 16 + lk + 4 * v) * RP + cb * 16 + lr] = acc[cb][v];
         }
     }
     __syncthreads();
-    if (blk < NB) {
+    if (wave < NB) {
       // C[i][j] = alpha sum_r' g[i][r'] U^T[j][r']
 #pragma unroll
       for (int cb = 0; cb < NB; ++cb) acc[cb] = mode_d4{0.0, 0.0, 0.0, 0.0};
@@ -873,7 +888,7 @@ k_g2c(int r, int ld_lt, int ld_le, const double *__restrict__ Aaa, const double 
         const int kr = ks * 4 + lk;
 #pragma unroll
         for (int cb = 0; cb < NB; ++cb)
-          acc[cb] = __builtin_amdgcn_mfma_f64_16x16x4f64(afr[ks], Us[(cb * 16 + lr) * RP + kr], acc[cb], 0, 0, 0);
+          acc[cb] = __builtin_amdgcn_mfma_f64_16x16x4f64(afr[ks], Z[(cb * 16 + lr) * RP + kr], acc[cb], 0, 0, 0);
       }
       double *dst = (side ? Cab : Caa) + (int64_t)row * r2;
 #pragma unroll
@@ -881,14 +896,12 @@ k_g2c(int r, int ld_lt, int ld_le, const double *__restrict__ Aaa, const double 
         const int j = cb * 16 + lr;
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
-          const int i = blk * 16 + lk + 4 * v;
+          const int i = wave * 16 + lk + 4 * v;
           if (i < r && j < r) dst[i * r + j] = alpha * acc[cb][v];
         }
       }
     }
-    if (!more) break;
-    __syncthreads();  // G and U^T are read before the next row overwrites them
-    row = next;
+    __syncthreads();  // G and U^T are read before the next item overwrites them
   }
 }
 
@@ -1807,25 +1820,26 @@ template <class O, int KS>
 static hipError_t launch_g2c_t(int r, const double *Aaa, const double *Aab, const double *Haa, const double *Hab,
                                const double *f, const double *g, double alpha, double *Caa, double *Cab, O Baa,
                                O BS, O BA, hipStream_t s) {
-  static int resident = 0;  // blocks the device holds at once
+  static int resident[kG2cMaxR + 1] = {};  // blocks the device holds at once, by r
   constexpr int NR = 16 * ((4 * KS + 15) / 16), RP = 4 * KS + 2;
   const size_t lds =
-      ((size_t)2 * NR * RP + std::max((size_t)3 * r * RP, (size_t)2 * NR * RP) + 2 * (size_t)r) * sizeof(double) +
+      ((size_t)NR * RP + std::max((size_t)2 * r * RP, (size_t)NR * RP) + 2 * (size_t)r) * sizeof(double) +
       pair_table_bytes(r);
   const void *fn = reinterpret_cast<const void *>(&k_g2c<O, KS>);
   hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   if (e != hipSuccess) return e;
-  if (resident == 0) {
+  if (resident[r] == 0) {
     int dev = 0, cus = 0, per_cu = 0;
     e = hipGetDevice(&dev);
     if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
-    if (e == hipSuccess) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, 512, lds);
+    if (e == hipSuccess) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, 256, lds);
     if (e != hipSuccess) return e;
-    resident = cus * std::max(per_cu, 1);
+    resident[r] = cus * std::max(per_cu, 1);
   }
-  const int nrow = r * r;
-  hipLaunchKernelGGL((k_g2c<O, KS>), dim3(std::min(nrow, resident)), dim3(512), lds, s, r, (int)ld_pair_lt(r),
-                     (int)ld_pair_le(r), Aaa, Aab, Haa, Hab, f, g, alpha, Caa, Cab, Baa, BS, BA, nrow);
+  const int nitem = 2 * r * r;  // (row, side)
+  hipLaunchKernelGGL((k_g2c<O, KS>), dim3(std::min(nitem, resident[r])), dim3(256), lds, s, r,
+                     (int)ld_pair_lt(r), (int)ld_pair_le(r), Aaa, Aab, Haa, Hab, f, g, alpha, Caa, Cab, Baa, BS,
+                     BA, nitem);
   return hipGetLastError();
 }
 
