@@ -23,6 +23,7 @@
 #include <cstdio>
 #include <cstring>
 #include <string>
+#include <initializer_list>
 #include <map>
 #include <utility>
 #include <vector>
@@ -933,27 +934,65 @@ extern "C" acse_status acse_residual_vjp(acse_ctx ctx, const acse_problem *prob,
     //                              M[(ij),(rs)]  = sum_(kl) Sb[ij,kl] G2[kl,rs]
     const int Akl_ij[4] = {2, 3, 0, 1};   // Sb[i,j,k,l] as rows (k,l), cols (i,j)
     const int Brs_kl[4] = {2, 3, 0, 1};   // X[k,l,r,s] as rows (r,s), cols (k,l)
-    // aa block
-    HIP_TRY(ctx, permute(prec, vop(0), true, Sbaa, ID, 1.0, nullptr, ID, 0.0, 0));
-    HIP_TRY(ctx, permute(prec, vop(1), true, Sbaa, Akl_ij, 1.0, nullptr, ID, 0.0, 0));
-    HIP_TRY(ctx, permute(prec, vop(2), true, w.Aaa, Brs_kl, 1.0, w.G2aa, Brs_kl, -1.0, 0));  // B = A - G2
-    HIP_TRY(ctx, permute(prec, vop(3), true, prob->d2aa, Brs_kl, 1.0, nullptr, ID, 0.0, 0));
-    HIP_TRY(ctx, permute(prec, vop(4), true, w.G2aa, Brs_kl, 1.0, nullptr, ID, 0.0, 0));
+    // aa block, packed over the pair antisymmetries (Gamma2_aa = 2 d2aa, B_aa = A_aa - G2_aa and
+    // G2_aa are antisymmetric within both pairs), pairs (a<b) in lt order:
+    //   Gb_aa enters only through its projection onto that subspace, whose value is
+    //     1/2 sum_(k<l) ZAA[(i<j),(k<l)] B[(k<l),(r<s)],  ZAA = Sb - Sb(i<->j) - Sb(k<->l) + Sb(both);
+    //   Bb_aa[(kl),(r<s)] = 2 sum_(i<j) (Sb[ij,kl] - Sb[ji,kl]) d2aa[ij,rs];
+    //   M_aa[(ij),(r<s)]  = sum_(k<l) (Sb[ij,kl] - Sb[ij,lk]) G2_aa[kl,rs].
+    const int nlt = npair_lt(r);
+    const int64_t ldlt = ld_pair_lt(r);
+    auto pack = [&](int q, int rows_lt, std::initializer_list<std::pair<const double *, std::pair<const int *, double>>> terms)
+        -> hipError_t {
+      PairPackArgs a{};
+      a.r = r;
+      a.rows_lt = rows_lt;
+      a.ld = ldlt;
+      for (const auto &t : terms) {
+        a.src[a.nterms] = t.first;
+        nat.map(t.second.first, a.st[a.nterms]);
+        a.c[a.nterms] = t.second.second;
+        ++a.nterms;
+      }
+      return launch_pack_pairs(prec, a, vop(q), s);
+    };
+    const int P_abcd[4] = {0, 1, 2, 3}, P_bacd[4] = {1, 0, 2, 3}, P_abdc[4] = {0, 1, 3, 2}, P_badc[4] = {1, 0, 3, 2};
+    const int P_cdab[4] = {2, 3, 0, 1}, P_dcab[4] = {2, 3, 1, 0};
+    HIP_TRY(ctx, pack(0, 1, {{Sbaa, {P_abcd, 1.0}}, {Sbaa, {P_bacd, -1.0}}, {Sbaa, {P_abdc, -1.0}},
+                             {Sbaa, {P_badc, 1.0}}}));
+    HIP_TRY(ctx, pack(1, 1, {{w.Aaa, {P_cdab, 1.0}}, {w.G2aa, {P_cdab, -1.0}}}));
+    HIP_TRY(ctx, pack(2, 0, {{Sbaa, {P_cdab, 1.0}}, {Sbaa, {P_dcab, -1.0}}}));
+    HIP_TRY(ctx, pack(3, 1, {{prob->d2aa, {P_cdab, 1.0}}}));
+    HIP_TRY(ctx, pack(4, 0, {{Sbaa, {P_abcd, 1.0}}, {Sbaa, {P_abdc, -1.0}}}));
+    HIP_TRY(ctx, pack(5, 1, {{w.G2aa, {P_cdab, 1.0}}}));
     // ab block
-    HIP_TRY(ctx, permute(prec, vop(5), true, Sbab, ID, 1.0, nullptr, ID, 0.0, 0));
-    HIP_TRY(ctx, permute(prec, vop(6), true, Sbab, Akl_ij, 1.0, nullptr, ID, 0.0, 0));
-    HIP_TRY(ctx, permute(prec, vop(7), true, w.Aab, Brs_kl, 1.0, w.G2ab, Brs_kl, -1.0, 0));
-    HIP_TRY(ctx, permute(prec, vop(8), true, prob->d2ab, Brs_kl, 1.0, nullptr, ID, 0.0, 0));
-    HIP_TRY(ctx, permute(prec, vop(9), true, w.G2ab, Brs_kl, 1.0, nullptr, ID, 0.0, 0));
+    HIP_TRY(ctx, permute(prec, vop(6), true, Sbab, ID, 1.0, nullptr, ID, 0.0, 0));
+    HIP_TRY(ctx, permute(prec, vop(7), true, Sbab, Akl_ij, 1.0, nullptr, ID, 0.0, 0));
+    HIP_TRY(ctx, permute(prec, vop(8), true, w.Aab, Brs_kl, 1.0, w.G2ab, Brs_kl, -1.0, 0));
+    HIP_TRY(ctx, permute(prec, vop(9), true, prob->d2ab, Brs_kl, 1.0, nullptr, ID, 0.0, 0));
+    HIP_TRY(ctx, permute(prec, vop(10), true, w.G2ab, Brs_kl, 1.0, nullptr, ID, 0.0, 0));
     GemmBatch b{};
     b.count = 6;
-    gemm_set(b, 0, 0, 2, 1.0, Gbaa, ID);
-    gemm_set(b, 1, 1, 3, 2.0, Bbaa, ID);   // Gamma2_aa = 2 d2aa
-    gemm_set(b, 2, 0, 4, 1.0, Maa, ID);
-    gemm_set(b, 3, 5, 7, 2.0, Gbab, ID);
-    gemm_set(b, 4, 6, 8, 4.0, Bbab, ID);   // 2 * Gamma2_ab = 4 d2ab
-    gemm_set(b, 5, 5, 9, 1.0, Mab, ID);
+    // packed products: C[m][n] = alpha sum_k A[m][k] B[n][k] into row-major [M][nlt] scratch
+    auto pair_set = [&](int q, int ia, int ib, double alpha, double *C, int M) {
+      GemmProb &P = b.p[q];
+      OperandRef a = vop(ia), bb = vop(ib);
+      P.A = a.hi; P.A2 = a.lo; P.B = bb.hi; P.B2 = bb.lo;
+      P.C = C; P.alpha = alpha;
+      P.M = M; P.N = nlt; P.Kp = gemm_kp(prec, nlt, (int)ldlt); P.ld = (int)ldlt; P.rdiv = 1;
+      P.sm1 = nlt; P.sm0 = 0; P.sn1 = 1; P.sn0 = 0;
+      P.ksplit = 1; P.kchunk = P.Kp; P.accumulate = 0;
+    };
+    pair_set(0, 0, 1, 0.5, T1, nlt);
+    pair_set(1, 2, 3, 2.0, T2, (int)r2);  // Gamma2_aa = 2 d2aa
+    pair_set(2, 4, 5, 1.0, T3, (int)r2);
+    gemm_set(b, 3, 6, 8, 2.0, Gbab, ID);
+    gemm_set(b, 4, 7, 9, 4.0, Bbab, ID);   // 2 * Gamma2_ab = 4 d2ab
+    gemm_set(b, 5, 6, 10, 1.0, Mab, ID);
     HIP_TRY(ctx, gemm_launch(prec, use_cfg, b, s));
+    HIP_TRY(ctx, launch_unpack_pairs(r, 1, T1, nlt, Gbaa, s));
+    HIP_TRY(ctx, launch_unpack_pairs(r, 0, T2, nlt, Bbaa, s));
+    HIP_TRY(ctx, launch_unpack_pairs(r, 0, T3, nlt, Maa, s));
   }
   // G2-bar = 4/3 (gamma x gamma) S-bar^T - B-bar;  A-bar += B-bar
   {

@@ -47,6 +47,27 @@ struct SlabContractArgs {
 hipError_t launch_contract42(int r, const ContractArgs &a, double *out, int accumulate, double *part,
                              hipStream_t s);
 
+// Pair-packed operand for the alpha-alpha pp adjoint products:
+//   out[m][q] = sum_t c[t] src[t][a st[t][0] + b st[t][1] + c st[t][2] + d st[t][3]]
+// row m = (a,b): a pair a < b in lt packing order (rows_lt = 1) or any (a,b)
+// with m = a r + b (rows_lt = 0); column q = (c,d), c < d in lt packing order,
+// q < r(r-1)/2; the columns r(r-1)/2 .. ld-1 are written as zero.
+struct PairPackArgs {
+  int r;
+  int rows_lt;
+  int64_t ld;
+  int nterms;  // 1..4
+  const double *src[4];
+  int64_t st[4][4];
+  double c[4];
+};
+hipError_t launch_pack_pairs(GemmPrec prec, const PairPackArgs &a, const OperandRef &out, hipStream_t s);
+// Natural r^4 tensor from a pair-packed product C (row stride ldc, columns lt
+// pairs (r,s), antisymmetric in (r,s)): rows lt pairs (p,q), antisymmetric in
+// (p,q) (rows_lt = 1), or all (p,q) (rows_lt = 0):
+//   out[p,q,r,s] = sign(p,q) sign(r,s) C[row][col], zero where p = q (rows_lt) or r = s.
+hipError_t launch_unpack_pairs(int r, int rows_lt, const double *C, int64_t ldc, double *out, hipStream_t s);
+
 hipError_t launch_vjp_pe(int r, const double *Saa, const double *Sab, double *Ppb, double *Pmb,
                          double *E3b, hipStream_t s);
 hipError_t launch_vjp_frank(int r, const double *fb, const double *g, double *Abaa, double *Abab,

@@ -474,6 +474,74 @@ hipError_t launch_permute4(GemmPrec prec, const PermArgs &a, const OperandRef &o
                            VOutBF16x3{static_cast<__bf16 *>(out.hi), static_cast<__bf16 *>(out.lo)}, s);
 }
 
+// ---------------------------------------------------------------------------
+// Pair packing and unpacking for the alpha-alpha pp adjoint products.  One
+// thread per output element; a packed row's consecutive columns (c, d), c < d,
+// run along d, so a source whose unit stride is position 3 is read in runs.
+// ---------------------------------------------------------------------------
+template <class O>
+__global__ void __launch_bounds__(256)
+k_pack_pairs(PairPackArgs a, int64_t rows, O out) {
+  const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (e >= rows * a.ld) return;
+  const int r = a.r;
+  const int64_t m = e / a.ld;
+  const int q = (int)(e - m * a.ld);
+  double v = 0.0;
+  if (q < npair_lt(r)) {
+    int ia, ib, ic, id;
+    if (a.rows_lt) {
+      unpair_lt(r, (int)m, ia, ib);
+    } else {
+      ia = (int)(m / r);
+      ib = (int)(m - (int64_t)ia * r);
+    }
+    unpair_lt(r, q, ic, id);
+    for (int t = 0; t < a.nterms; ++t)
+      v += a.c[t] * a.src[t][ia * a.st[t][0] + ib * a.st[t][1] + ic * a.st[t][2] + id * a.st[t][3]];
+  }
+  out.put(e, v);
+}
+
+__global__ void __launch_bounds__(256)
+k_unpack_pairs(int r, int rows_lt, const double *__restrict__ C, int64_t ldc, double *__restrict__ out) {
+  const int64_t r2 = (int64_t)r * r;
+  const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (e >= r2 * r2) return;
+  const int64_t rowpq = e / r2, colrs = e - rowpq * r2;
+  const int p = (int)(rowpq / r), q = (int)(rowpq - (int64_t)p * r);
+  const int rr = (int)(colrs / r), ss = (int)(colrs - (int64_t)rr * r);
+  double v = 0.0;
+  if (rr != ss && !(rows_lt && p == q)) {
+    const int64_t row = rows_lt ? pair_lt(r, min(p, q), max(p, q)) : rowpq;
+    const int col = pair_lt(r, min(rr, ss), max(rr, ss));
+    v = C[row * ldc + col];
+    if (rr > ss) v = -v;
+    if (rows_lt && p > q) v = -v;
+  }
+  out[e] = v;
+}
+
+hipError_t launch_pack_pairs(GemmPrec prec, const PairPackArgs &a, const OperandRef &out, hipStream_t s) {
+  if (a.nterms < 1 || a.nterms > 4 || a.ld < npair_lt(a.r)) return hipErrorInvalidValue;
+  const int64_t rows = a.rows_lt ? npair_lt(a.r) : (int64_t)a.r * a.r;
+  const dim3 grid = vgrid(rows * a.ld);
+  if (prec == GEMM_F64)
+    hipLaunchKernelGGL((k_pack_pairs<VOutF64>), grid, dim3(256), 0, s, a, rows, VOutF64{static_cast<double *>(out.hi)});
+  else if (prec == GEMM_F32)
+    hipLaunchKernelGGL((k_pack_pairs<VOutF32>), grid, dim3(256), 0, s, a, rows, VOutF32{static_cast<float *>(out.hi)});
+  else
+    hipLaunchKernelGGL((k_pack_pairs<VOutBF16x3>), grid, dim3(256), 0, s, a, rows,
+                       VOutBF16x3{static_cast<__bf16 *>(out.hi), static_cast<__bf16 *>(out.lo)});
+  return hipGetLastError();
+}
+
+hipError_t launch_unpack_pairs(int r, int rows_lt, const double *C, int64_t ldc, double *out, hipStream_t s) {
+  const int64_t r2 = (int64_t)r * r;
+  hipLaunchKernelGGL(k_unpack_pairs, vgrid(r2 * r2), dim3(256), 0, s, r, rows_lt, C, ldc, out);
+  return hipGetLastError();
+}
+
 hipError_t launch_contract42(int r, const ContractArgs &a, double *out, int accumulate, double *part,
                              hipStream_t s) {
   // slab form when every term has x, u in the first index pair and y, v in the
