@@ -109,7 +109,9 @@ typedef struct {
  * (otherwise r > 52), without its mirrored-row staging (otherwise r > 82) and
  * without its pair-index tables (otherwise r in 80..82 and r > 94); the
  * row-chunked assembly (otherwise r > 81); the mode-product kernel in its
- * r > 64 shape and the Gram kernel in its r > 80 shape).  Same results up to
+ * r > 64 shape and the Gram kernel in its r > 80 shape; in the adjoint, the
+ * alpha-beta pp products packed over the pair-exchange symmetry (otherwise
+ * r >= 40)).  Same results up to
  * rounding order; meant for verifying those kernels at small r.  Other bits
  * are an ACSE_ERR_ARG. */
 #define ACSE_FLAG_GENERAL_KERNELS 1

@@ -40,6 +40,7 @@ constexpr int kNat = 26;     // natural r^4 arrays in Workspace
 constexpr int kNumOps = 12;  // GEMM operand buffers in Workspace
 constexpr int kProbsPerMap = 6;  // pair-index products of one residual map
 constexpr int kTuneReps = 5;     // timed repetitions per tile configuration in the autotuners
+constexpr int kAbPackMinR = 40;  // smallest r whose alpha-beta pp adjoint products run packed
 
 struct Workspace {
   // natural FP64 r^4 arrays
@@ -932,67 +933,136 @@ extern "C" acse_status acse_residual_vjp(acse_ctx ctx, const acse_problem *prob,
     // G-bar = Z-bar B^T-products:  Gb[(ij),(rs)] = sum_(kl) Sb[ij,kl] B[kl,rs]
     //                              Bb[(kl),(rs)] = sum_(ij) Sb[ij,kl] Gamma2[ij,rs]
     //                              M[(ij),(rs)]  = sum_(kl) Sb[ij,kl] G2[kl,rs]
-    const int Akl_ij[4] = {2, 3, 0, 1};   // Sb[i,j,k,l] as rows (k,l), cols (i,j)
-    const int Brs_kl[4] = {2, 3, 0, 1};   // X[k,l,r,s] as rows (r,s), cols (k,l)
-    // aa block, packed over the pair antisymmetries (Gamma2_aa = 2 d2aa, B_aa = A_aa - G2_aa and
-    // G2_aa are antisymmetric within both pairs), pairs (a<b) in lt order:
+    // all packed over the pair symmetries of Gamma2, B and G2 (pairs (a<b) or
+    // (a<=b) in packing order; Gamma2_aa = 2 d2aa, Gamma2_ab = 2 d2ab):
+    //  alpha-alpha (Gamma2, B, G2 antisymmetric within both pairs):
     //   Gb_aa enters only through its projection onto that subspace, whose value is
     //     1/2 sum_(k<l) ZAA[(i<j),(k<l)] B[(k<l),(r<s)],  ZAA = Sb - Sb(i<->j) - Sb(k<->l) + Sb(both);
-    //   Bb_aa[(kl),(r<s)] = 2 sum_(i<j) (Sb[ij,kl] - Sb[ji,kl]) d2aa[ij,rs];
+    //   Bb_aa[(kl),(r<s)] = 2 sum_(i<j) (Sb[ij,kl] - Sb[ji,kl]) Gamma2_aa[ij,rs];
     //   M_aa[(ij),(r<s)]  = sum_(k<l) (Sb[ij,kl] - Sb[ij,lk]) G2_aa[kl,rs].
-    const int nlt = npair_lt(r);
-    const int64_t ldlt = ld_pair_lt(r);
-    auto pack = [&](int q, int rows_lt, std::initializer_list<std::pair<const double *, std::pair<const int *, double>>> terms)
-        -> hipError_t {
+    //  alpha-beta (Gamma2, B, G2 invariant under (ij)(kl) -> (ji)(lk)): each
+    //  product splits by r <-> s into X+- = X[.,rs] +- X[.,sr], X = (X+ + X-)/2,
+    //  with the summed pair packed as k <= l (+) and k < l (-):
+    //   Gb_ab enters only through its projection onto that symmetry, whose value
+    //     is 2 Zt B with Zt = (Sb + Sb[ji,lk]) / 2; its + part is symmetric and
+    //     its - part antisymmetric in (i,j), so rows are packed too;
+    //   Bb_ab+- = 2 sum_(i<=j / i<j) (Sb[ij,kl] +- Sb[ji,kl]) Gamma2_ab+-[ij,rs] (i = j once);
+    //   M_ab+-  = sum_(k<=l / k<l) (Sb[ij,kl] +- Sb[ij,lk]) G2_ab+-[kl,rs] (k = l once).
+    const int nlt = npair_lt(r), nle = npair_le(r);
+    const int64_t ldlt = ld_pair_lt(r), ldle = ld_pair_le(r);
+    struct PackTerm { const double *src; const int *map; double c; int offdiag; };
+    auto pack = [&](int q, int rows_mode, int k_le, std::initializer_list<PackTerm> terms) -> hipError_t {
       PairPackArgs a{};
       a.r = r;
-      a.rows_lt = rows_lt;
-      a.ld = ldlt;
-      for (const auto &t : terms) {
-        a.src[a.nterms] = t.first;
-        nat.map(t.second.first, a.st[a.nterms]);
-        a.c[a.nterms] = t.second.second;
+      a.rows_mode = rows_mode;
+      a.k_le = k_le;
+      a.ld = k_le ? ldle : ldlt;
+      for (const PackTerm &t : terms) {
+        a.src[a.nterms] = t.src;
+        nat.map(t.map, a.st[a.nterms]);
+        a.c[a.nterms] = t.c;
+        a.offdiag[a.nterms] = t.offdiag;
         ++a.nterms;
       }
       return launch_pack_pairs(prec, a, vop(q), s);
     };
-    const int P_abcd[4] = {0, 1, 2, 3}, P_bacd[4] = {1, 0, 2, 3}, P_abdc[4] = {0, 1, 3, 2}, P_badc[4] = {1, 0, 3, 2};
-    const int P_cdab[4] = {2, 3, 0, 1}, P_dcab[4] = {2, 3, 1, 0};
-    HIP_TRY(ctx, pack(0, 1, {{Sbaa, {P_abcd, 1.0}}, {Sbaa, {P_bacd, -1.0}}, {Sbaa, {P_abdc, -1.0}},
-                             {Sbaa, {P_badc, 1.0}}}));
-    HIP_TRY(ctx, pack(1, 1, {{w.Aaa, {P_cdab, 1.0}}, {w.G2aa, {P_cdab, -1.0}}}));
-    HIP_TRY(ctx, pack(2, 0, {{Sbaa, {P_cdab, 1.0}}, {Sbaa, {P_dcab, -1.0}}}));
-    HIP_TRY(ctx, pack(3, 1, {{prob->d2aa, {P_cdab, 1.0}}}));
-    HIP_TRY(ctx, pack(4, 0, {{Sbaa, {P_abcd, 1.0}}, {Sbaa, {P_abdc, -1.0}}}));
-    HIP_TRY(ctx, pack(5, 1, {{w.G2aa, {P_cdab, 1.0}}}));
-    // ab block
-    HIP_TRY(ctx, permute(prec, vop(6), true, Sbab, ID, 1.0, nullptr, ID, 0.0, 0));
-    HIP_TRY(ctx, permute(prec, vop(7), true, Sbab, Akl_ij, 1.0, nullptr, ID, 0.0, 0));
-    HIP_TRY(ctx, permute(prec, vop(8), true, w.Aab, Brs_kl, 1.0, w.G2ab, Brs_kl, -1.0, 0));
-    HIP_TRY(ctx, permute(prec, vop(9), true, prob->d2ab, Brs_kl, 1.0, nullptr, ID, 0.0, 0));
-    HIP_TRY(ctx, permute(prec, vop(10), true, w.G2ab, Brs_kl, 1.0, nullptr, ID, 0.0, 0));
-    GemmBatch b{};
-    b.count = 6;
-    // packed products: C[m][n] = alpha sum_k A[m][k] B[n][k] into row-major [M][nlt] scratch
-    auto pair_set = [&](int q, int ia, int ib, double alpha, double *C, int M) {
+    // index maps: term X[...] of the letters (a,b) = packed row pair, (c,d) = packed K pair
+    const int abcd[4] = {0, 1, 2, 3}, bacd[4] = {1, 0, 2, 3}, abdc[4] = {0, 1, 3, 2}, badc[4] = {1, 0, 3, 2};
+    const int cdab[4] = {2, 3, 0, 1}, dcab[4] = {2, 3, 1, 0}, cdba[4] = {3, 2, 0, 1};
+    // packed products: C[m][n] = alpha sum_k A[m][k] B[n][k] into row-major [M][N] scratch
+    auto pair_set = [&](GemmBatch &b, int q, int ia, int ib, double alpha, double *C, int M, int N, int k_le) {
       GemmProb &P = b.p[q];
       OperandRef a = vop(ia), bb = vop(ib);
+      const int K = k_le ? nle : nlt, ldk = (int)(k_le ? ldle : ldlt);
       P.A = a.hi; P.A2 = a.lo; P.B = bb.hi; P.B2 = bb.lo;
       P.C = C; P.alpha = alpha;
-      P.M = M; P.N = nlt; P.Kp = gemm_kp(prec, nlt, (int)ldlt); P.ld = (int)ldlt; P.rdiv = 1;
-      P.sm1 = nlt; P.sm0 = 0; P.sn1 = 1; P.sn0 = 0;
+      P.M = M; P.N = N; P.Kp = gemm_kp(prec, K, ldk); P.ld = ldk; P.rdiv = 1;
+      P.sm1 = N; P.sm0 = 0; P.sn1 = 1; P.sn0 = 0;
       P.ksplit = 1; P.kchunk = P.Kp; P.accumulate = 0;
     };
-    pair_set(0, 0, 1, 0.5, T1, nlt);
-    pair_set(1, 2, 3, 2.0, T2, (int)r2);  // Gamma2_aa = 2 d2aa
-    pair_set(2, 4, 5, 1.0, T3, (int)r2);
-    gemm_set(b, 3, 6, 8, 2.0, Gbab, ID);
-    gemm_set(b, 4, 7, 9, 4.0, Bbab, ID);   // 2 * Gamma2_ab = 4 d2ab
-    gemm_set(b, 5, 6, 10, 1.0, Mab, ID);
-    HIP_TRY(ctx, gemm_launch(prec, use_cfg, b, s));
-    HIP_TRY(ctx, launch_unpack_pairs(r, 1, T1, nlt, Gbaa, s));
-    HIP_TRY(ctx, launch_unpack_pairs(r, 0, T2, nlt, Bbaa, s));
-    HIP_TRY(ctx, launch_unpack_pairs(r, 0, T3, nlt, Maa, s));
+    const int R2 = (int)r2;
+    double *Gp = T4, *Gm = T4 + (int64_t)nle * nle;  // Gb_ab +- (rows packed)
+    // Below kAbPackMinR the packing passes and the second launch cost more than
+    // the alpha-beta flops they save: those products run unpacked there (the
+    // general-kernel option takes the packed form at every r).
+    const bool pack_ab = r >= kAbPackMinR || ctx->general;
+    if (!pack_ab) {
+      const int Akl_ij[4] = {2, 3, 0, 1};   // Sb[i,j,k,l] as rows (k,l), cols (i,j)
+      const int Brs_kl[4] = {2, 3, 0, 1};   // X[k,l,r,s] as rows (r,s), cols (k,l)
+      HIP_TRY(ctx, pack(0, 1, 0, {{Sbaa, abcd, 1.0, 0}, {Sbaa, bacd, -1.0, 0}, {Sbaa, abdc, -1.0, 0},
+                                  {Sbaa, badc, 1.0, 0}}));
+      HIP_TRY(ctx, pack(1, 1, 0, {{w.Aaa, cdab, 1.0, 0}, {w.G2aa, cdab, -1.0, 0}}));
+      HIP_TRY(ctx, pack(2, 0, 0, {{Sbaa, cdab, 1.0, 0}, {Sbaa, dcab, -1.0, 0}}));
+      HIP_TRY(ctx, pack(3, 1, 0, {{prob->d2aa, cdab, 1.0, 0}}));
+      HIP_TRY(ctx, pack(4, 0, 0, {{Sbaa, abcd, 1.0, 0}, {Sbaa, abdc, -1.0, 0}}));
+      HIP_TRY(ctx, pack(5, 1, 0, {{w.G2aa, cdab, 1.0, 0}}));
+      HIP_TRY(ctx, permute(prec, vop(6), true, Sbab, ID, 1.0, nullptr, ID, 0.0, 0));
+      HIP_TRY(ctx, permute(prec, vop(7), true, Sbab, Akl_ij, 1.0, nullptr, ID, 0.0, 0));
+      HIP_TRY(ctx, permute(prec, vop(8), true, w.Aab, Brs_kl, 1.0, w.G2ab, Brs_kl, -1.0, 0));
+      HIP_TRY(ctx, permute(prec, vop(9), true, prob->d2ab, Brs_kl, 1.0, nullptr, ID, 0.0, 0));
+      HIP_TRY(ctx, permute(prec, vop(10), true, w.G2ab, Brs_kl, 1.0, nullptr, ID, 0.0, 0));
+      GemmBatch b{};
+      b.count = 6;
+      pair_set(b, 0, 0, 1, 0.5, T1, nlt, nlt, 0);
+      pair_set(b, 1, 2, 3, 2.0, T2, R2, nlt, 0);
+      pair_set(b, 2, 4, 5, 1.0, T3, R2, nlt, 0);
+      gemm_set(b, 3, 6, 8, 2.0, Gbab, ID);
+      gemm_set(b, 4, 7, 9, 4.0, Bbab, ID);   // 2 * Gamma2_ab = 4 d2ab
+      gemm_set(b, 5, 6, 10, 1.0, Mab, ID);
+      HIP_TRY(ctx, gemm_launch(prec, use_cfg, b, s));
+      HIP_TRY(ctx, launch_unpack_pairs(r, 1, T1, nlt, Gbaa, s));
+      HIP_TRY(ctx, launch_unpack_pairs(r, 0, T2, nlt, Bbaa, s));
+      HIP_TRY(ctx, launch_unpack_pairs(r, 0, T3, nlt, Maa, s));
+    }
+    if (pack_ab) {
+      HIP_TRY(ctx, pack(0, 1, 0, {{Sbaa, abcd, 1.0, 0}, {Sbaa, bacd, -1.0, 0}, {Sbaa, abdc, -1.0, 0},
+                                  {Sbaa, badc, 1.0, 0}}));
+      HIP_TRY(ctx, pack(1, 1, 0, {{w.Aaa, cdab, 1.0, 0}, {w.G2aa, cdab, -1.0, 0}}));
+      HIP_TRY(ctx, pack(2, 0, 0, {{Sbaa, cdab, 1.0, 0}, {Sbaa, dcab, -1.0, 0}}));
+      HIP_TRY(ctx, pack(3, 1, 0, {{prob->d2aa, cdab, 1.0, 0}}));
+      HIP_TRY(ctx, pack(4, 0, 0, {{Sbaa, abcd, 1.0, 0}, {Sbaa, abdc, -1.0, 0}}));
+      HIP_TRY(ctx, pack(5, 1, 0, {{w.G2aa, cdab, 1.0, 0}}));
+      HIP_TRY(ctx, pack(6, 2, 1, {{Sbab, abcd, 0.5, 0}, {Sbab, badc, 0.5, 0}, {Sbab, abdc, 0.5, 1},
+                                  {Sbab, bacd, 0.5, 1}}));
+      HIP_TRY(ctx, pack(7, 2, 1, {{w.Aab, cdab, 1.0, 0}, {w.Aab, cdba, 1.0, 0}, {w.G2ab, cdab, -1.0, 0},
+                                  {w.G2ab, cdba, -1.0, 0}}));
+      HIP_TRY(ctx, pack(8, 1, 0, {{Sbab, abcd, 0.5, 0}, {Sbab, badc, 0.5, 0}, {Sbab, abdc, -0.5, 0},
+                                  {Sbab, bacd, -0.5, 0}}));
+      HIP_TRY(ctx, pack(9, 1, 0, {{w.Aab, cdab, 1.0, 0}, {w.Aab, cdba, -1.0, 0}, {w.G2ab, cdab, -1.0, 0},
+                                  {w.G2ab, cdba, 1.0, 0}}));
+      GemmBatch b{};
+      b.count = 5;
+      pair_set(b, 0, 0, 1, 0.5, T1, nlt, nlt, 0);
+      pair_set(b, 1, 2, 3, 2.0, T2, R2, nlt, 0);
+      pair_set(b, 2, 4, 5, 1.0, T3, R2, nlt, 0);
+      pair_set(b, 3, 6, 7, 2.0, Gp, nle, nle, 1);
+      pair_set(b, 4, 8, 9, 2.0, Gm, nlt, nlt, 0);
+      HIP_TRY(ctx, gemm_launch(prec, use_cfg, b, s));
+      HIP_TRY(ctx, launch_unpack_pairs(r, 1, T1, nlt, Gbaa, s));
+      HIP_TRY(ctx, launch_unpack_pairs(r, 0, T2, nlt, Bbaa, s));
+      HIP_TRY(ctx, launch_unpack_pairs(r, 0, T3, nlt, Maa, s));
+      HIP_TRY(ctx, launch_unpack_pm(r, 1, Gp, nle, Gm, nlt, Gbab, s));
+    }
+    if (pack_ab) {
+      double *Bp = T1, *Bm = T1 + (int64_t)r2 * nle, *Mp = T2, *Mm = T2 + (int64_t)r2 * nle;
+      HIP_TRY(ctx, pack(0, 0, 1, {{Sbab, cdab, 1.0, 0}, {Sbab, dcab, 1.0, 1}}));
+      HIP_TRY(ctx, pack(1, 2, 1, {{prob->d2ab, cdab, 1.0, 0}, {prob->d2ab, cdba, 1.0, 0}}));
+      HIP_TRY(ctx, pack(2, 0, 0, {{Sbab, cdab, 1.0, 0}, {Sbab, dcab, -1.0, 0}}));
+      HIP_TRY(ctx, pack(3, 1, 0, {{prob->d2ab, cdab, 1.0, 0}, {prob->d2ab, cdba, -1.0, 0}}));
+      HIP_TRY(ctx, pack(4, 0, 1, {{Sbab, abcd, 1.0, 0}, {Sbab, abdc, 1.0, 1}}));
+      HIP_TRY(ctx, pack(5, 2, 1, {{w.G2ab, cdab, 1.0, 0}, {w.G2ab, cdba, 1.0, 0}}));
+      HIP_TRY(ctx, pack(6, 0, 0, {{Sbab, abcd, 1.0, 0}, {Sbab, abdc, -1.0, 0}}));
+      HIP_TRY(ctx, pack(7, 1, 0, {{w.G2ab, cdab, 1.0, 0}, {w.G2ab, cdba, -1.0, 0}}));
+      GemmBatch b{};
+      b.count = 4;
+      pair_set(b, 0, 0, 1, 4.0, Bp, R2, nle, 1);  // 2 Gamma2_ab = 4 d2ab
+      pair_set(b, 1, 2, 3, 4.0, Bm, R2, nlt, 0);
+      pair_set(b, 2, 4, 5, 1.0, Mp, R2, nle, 1);
+      pair_set(b, 3, 6, 7, 1.0, Mm, R2, nlt, 0);
+      HIP_TRY(ctx, gemm_launch(prec, use_cfg, b, s));
+      HIP_TRY(ctx, launch_unpack_pm(r, 0, Bp, nle, Bm, nlt, Bbab, s));
+      HIP_TRY(ctx, launch_unpack_pm(r, 0, Mp, nle, Mm, nlt, Mab, s));
+    }
   }
   // G2-bar = 4/3 (gamma x gamma) S-bar^T - B-bar;  A-bar += B-bar
   {

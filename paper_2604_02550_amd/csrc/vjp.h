@@ -47,19 +47,22 @@ struct SlabContractArgs {
 hipError_t launch_contract42(int r, const ContractArgs &a, double *out, int accumulate, double *part,
                              hipStream_t s);
 
-// Pair-packed operand for the alpha-alpha pp adjoint products:
+// Pair-packed operand of the pp adjoint products:
 //   out[m][q] = sum_t c[t] src[t][a st[t][0] + b st[t][1] + c st[t][2] + d st[t][3]]
-// row m = (a,b): a pair a < b in lt packing order (rows_lt = 1) or any (a,b)
-// with m = a r + b (rows_lt = 0); column q = (c,d), c < d in lt packing order,
-// q < r(r-1)/2; the columns r(r-1)/2 .. ld-1 are written as zero.
+// row m = (a,b): any (a,b) with m = a r + b (rows_mode 0), a pair a < b
+// (rows_mode 1) or a <= b (rows_mode 2) in packing order; column q = (c,d),
+// c < d (k_le 0) or c <= d (k_le 1) in packing order; a term with offdiag[t]
+// set is skipped where c = d.  Columns past the pair count up to ld are zero.
 struct PairPackArgs {
   int r;
-  int rows_lt;
+  int rows_mode;
+  int k_le;
   int64_t ld;
   int nterms;  // 1..4
   const double *src[4];
   int64_t st[4][4];
   double c[4];
+  int offdiag[4];
 };
 hipError_t launch_pack_pairs(GemmPrec prec, const PairPackArgs &a, const OperandRef &out, hipStream_t s);
 // Natural r^4 tensor from a pair-packed product C (row stride ldc, columns lt
@@ -67,6 +70,13 @@ hipError_t launch_pack_pairs(GemmPrec prec, const PairPackArgs &a, const Operand
 // (p,q) (rows_lt = 1), or all (p,q) (rows_lt = 0):
 //   out[p,q,r,s] = sign(p,q) sign(r,s) C[row][col], zero where p = q (rows_lt) or r = s.
 hipError_t launch_unpack_pairs(int r, int rows_lt, const double *C, int64_t ldc, double *out, hipStream_t s);
+// Natural r^4 tensor from the two parts of a product split by the exchange
+// r <-> s: Cp (columns le pairs, symmetric in (r,s)) and Cm (columns lt pairs,
+// antisymmetric); rows all (p,q) (rows_packed 0), or le pairs of Cp and lt
+// pairs of Cm with the same symmetry in (p,q) (rows_packed 1):
+//   out[p,q,r,s] = (Cp[.][.] + sign(p,q) sign(r,s) Cm[.][.]) / 2, the Cm part zero where r = s or p = q.
+hipError_t launch_unpack_pm(int r, int rows_packed, const double *Cp, int64_t ldp, const double *Cm, int64_t ldm,
+                            double *out, hipStream_t s);
 
 hipError_t launch_vjp_pe(int r, const double *Saa, const double *Sab, double *Ppb, double *Pmb,
                          double *E3b, hipStream_t s);

@@ -481,24 +481,28 @@ hipError_t launch_permute4(GemmPrec prec, const PermArgs &a, const OperandRef &o
 // ---------------------------------------------------------------------------
 template <class O>
 __global__ void __launch_bounds__(256)
-k_pack_pairs(PairPackArgs a, int64_t rows, O out) {
+k_pack_pairs(PairPackArgs a, int64_t rows, int64_t npk, O out) {
   const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
   if (e >= rows * a.ld) return;
   const int r = a.r;
   const int64_t m = e / a.ld;
   const int q = (int)(e - m * a.ld);
   double v = 0.0;
-  if (q < npair_lt(r)) {
+  if (q < npk) {
     int ia, ib, ic, id;
-    if (a.rows_lt) {
+    if (a.rows_mode == 1) {
       unpair_lt(r, (int)m, ia, ib);
+    } else if (a.rows_mode == 2) {
+      unpair_le(r, (int)m, ia, ib);
     } else {
       ia = (int)(m / r);
       ib = (int)(m - (int64_t)ia * r);
     }
-    unpair_lt(r, q, ic, id);
+    if (a.k_le) unpair_le(r, q, ic, id);
+    else unpair_lt(r, q, ic, id);
     for (int t = 0; t < a.nterms; ++t)
-      v += a.c[t] * a.src[t][ia * a.st[t][0] + ib * a.st[t][1] + ic * a.st[t][2] + id * a.st[t][3]];
+      if (!(a.offdiag[t] && ic == id))
+        v += a.c[t] * a.src[t][ia * a.st[t][0] + ib * a.st[t][1] + ic * a.st[t][2] + id * a.st[t][3]];
   }
   out.put(e, v);
 }
@@ -523,16 +527,48 @@ k_unpack_pairs(int r, int rows_lt, const double *__restrict__ C, int64_t ldc, do
 }
 
 hipError_t launch_pack_pairs(GemmPrec prec, const PairPackArgs &a, const OperandRef &out, hipStream_t s) {
-  if (a.nterms < 1 || a.nterms > 4 || a.ld < npair_lt(a.r)) return hipErrorInvalidValue;
-  const int64_t rows = a.rows_lt ? npair_lt(a.r) : (int64_t)a.r * a.r;
+  const int64_t npk = a.k_le ? npair_le(a.r) : npair_lt(a.r);
+  if (a.nterms < 1 || a.nterms > 4 || a.ld < npk || a.rows_mode < 0 || a.rows_mode > 2) return hipErrorInvalidValue;
+  const int64_t rows = a.rows_mode == 1 ? npair_lt(a.r) : a.rows_mode == 2 ? npair_le(a.r) : (int64_t)a.r * a.r;
   const dim3 grid = vgrid(rows * a.ld);
   if (prec == GEMM_F64)
-    hipLaunchKernelGGL((k_pack_pairs<VOutF64>), grid, dim3(256), 0, s, a, rows, VOutF64{static_cast<double *>(out.hi)});
+    hipLaunchKernelGGL((k_pack_pairs<VOutF64>), grid, dim3(256), 0, s, a, rows, npk,
+                       VOutF64{static_cast<double *>(out.hi)});
   else if (prec == GEMM_F32)
-    hipLaunchKernelGGL((k_pack_pairs<VOutF32>), grid, dim3(256), 0, s, a, rows, VOutF32{static_cast<float *>(out.hi)});
+    hipLaunchKernelGGL((k_pack_pairs<VOutF32>), grid, dim3(256), 0, s, a, rows, npk,
+                       VOutF32{static_cast<float *>(out.hi)});
   else
-    hipLaunchKernelGGL((k_pack_pairs<VOutBF16x3>), grid, dim3(256), 0, s, a, rows,
+    hipLaunchKernelGGL((k_pack_pairs<VOutBF16x3>), grid, dim3(256), 0, s, a, rows, npk,
                        VOutBF16x3{static_cast<__bf16 *>(out.hi), static_cast<__bf16 *>(out.lo)});
+  return hipGetLastError();
+}
+
+__global__ void __launch_bounds__(256)
+k_unpack_pm(int r, int rows_packed, const double *__restrict__ Cp, int64_t ldp, const double *__restrict__ Cm,
+            int64_t ldm, double *__restrict__ out) {
+  const int64_t r2 = (int64_t)r * r;
+  const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (e >= r2 * r2) return;
+  const int64_t rowpq = e / r2, colrs = e - rowpq * r2;
+  const int p = (int)(rowpq / r), q = (int)(rowpq - (int64_t)p * r);
+  const int rr = (int)(colrs / r), ss = (int)(colrs - (int64_t)rr * r);
+  const int a = min(p, q), b = max(p, q), c = min(rr, ss), d = max(rr, ss);
+  const int64_t rowp = rows_packed ? pair_le(r, a, b) : rowpq;
+  double v = Cp[rowp * ldp + pair_le(r, c, d)];
+  if (c != d && !(rows_packed && a == b)) {
+    const int64_t rowm = rows_packed ? pair_lt(r, a, b) : rowpq;
+    double w = Cm[rowm * ldm + pair_lt(r, c, d)];
+    if (rr > ss) w = -w;
+    if (rows_packed && p > q) w = -w;
+    v += w;
+  }
+  out[e] = 0.5 * v;
+}
+
+hipError_t launch_unpack_pm(int r, int rows_packed, const double *Cp, int64_t ldp, const double *Cm, int64_t ldm,
+                            double *out, hipStream_t s) {
+  const int64_t r2 = (int64_t)r * r;
+  hipLaunchKernelGGL(k_unpack_pm, vgrid(r2 * r2), dim3(256), 0, s, r, rows_packed, Cp, ldp, Cm, ldm, out);
   return hipGetLastError();
 }
 

@@ -86,15 +86,20 @@ def test_residual_vjp_fp64_vs_oracle(ctx, name):
         assert maxrel(got[k], ref[k]) < TOL64, (k, maxrel(got[k], ref[k]))
 
 
-def test_residual_vjp_general_kernels(acse, ctx):
-    """The adjoint with the general-size G2 kernel (ACSE_FLAG_GENERAL_KERNELS)."""
+@pytest.mark.parametrize("precision,tol", [("fp64", TOL64), ("fp32", 1e-5), ("bf16x3", 5e-5)])
+def test_residual_vjp_general_kernels(acse, ctx, precision, tol):
+    """The adjoint with the general-size kernels (ACSE_FLAG_GENERAL_KERNELS): the
+    G2 kernel that stores G2, and the alpha-beta pp adjoint products packed
+    over the pair-exchange symmetry (the form used from r = 40 on), in every
+    precision of the contractions."""
     p = PROBLEMS["r13"]()
+    print(f"[vjp_general] r13 {precision}", flush=True)
     Rb = gen.cotangent(np.random.default_rng(25), p["r"])
     ref = adj.residual_vjp(p["h"], p["V"], p["N"], p["gamma"], p["d2aa"], p["d2ab"], *Rb)
     out = ctx.residual_vjp(p["h"], p["V"], p["gamma"], p["d2aa"], p["d2ab"], p["N"] // 2, Rb[0], Rb[1],
-                           flags=acse.FLAG_GENERAL_KERNELS)
+                           precision=precision, flags=acse.FLAG_GENERAL_KERNELS)
     for k, x in zip(KEYS, out):
-        assert rel(cpu(x), ref[k]) < TOL64, k
+        assert rel(cpu(x), ref[k]) < tol, k
 
 
 @pytest.mark.parametrize("name", list(PROBLEMS))
