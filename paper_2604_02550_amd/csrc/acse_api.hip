@@ -968,7 +968,6 @@ extern "C" acse_status acse_residual_vjp(acse_ctx ctx, const acse_problem *prob,
     };
     // index maps: term X[...] of the letters (a,b) = packed row pair, (c,d) = packed K pair
     const int abcd[4] = {0, 1, 2, 3}, bacd[4] = {1, 0, 2, 3}, abdc[4] = {0, 1, 3, 2}, badc[4] = {1, 0, 3, 2};
-    const int cdab[4] = {2, 3, 0, 1}, dcab[4] = {2, 3, 1, 0}, cdba[4] = {3, 2, 0, 1};
     // packed products: C[m][n] = alpha sum_k A[m][k] B[n][k] into row-major [M][N] scratch
     auto pair_set = [&](GemmBatch &b, int q, int ia, int ib, double alpha, double *C, int M, int N, int k_le) {
       GemmProb &P = b.p[q];
@@ -980,6 +979,29 @@ extern "C" acse_status acse_residual_vjp(acse_ctx ctx, const acse_problem *prob,
       P.sm1 = N; P.sm0 = 0; P.sn1 = 1; P.sn0 = 0;
       P.ksplit = 1; P.kchunk = P.Kp; P.accumulate = 0;
     };
+    // The packing passes read the summed pair along the fast source index: a
+    // source whose summed pair is its leading pair is first exchanged
+    // ((ij) <-> (kl), X^T[a,b,c,d] = X[c,d,a,b]) into a buffer that is free
+    // until the products' results are unpacked.
+    const int XT[4] = {2, 3, 0, 1};
+    auto exch = [&](double *dst, const double *x, const double *y, double cy) -> hipError_t {
+      return permute(GEMM_F64, natref(dst), false, x, XT, 1.0, y, XT, cy, 0);
+    };
+    auto pack_aa = [&]() -> hipError_t {
+      double *SbaaT = Gbaa, *BaaT = Bbaa, *G2aaT = Maa, *DaaT = Vraw;
+      hipError_t e;
+      if ((e = exch(SbaaT, Sbaa, nullptr, 0.0)) != hipSuccess) return e;
+      if ((e = exch(BaaT, w.Aaa, w.G2aa, -1.0)) != hipSuccess) return e;
+      if ((e = exch(G2aaT, w.G2aa, nullptr, 0.0)) != hipSuccess) return e;
+      if ((e = exch(DaaT, prob->d2aa, nullptr, 0.0)) != hipSuccess) return e;
+      if ((e = pack(0, 1, 0, {{Sbaa, abcd, 1.0, 0}, {Sbaa, bacd, -1.0, 0}, {Sbaa, abdc, -1.0, 0},
+                              {Sbaa, badc, 1.0, 0}})) != hipSuccess) return e;
+      if ((e = pack(1, 1, 0, {{BaaT, abcd, 1.0, 0}})) != hipSuccess) return e;
+      if ((e = pack(2, 0, 0, {{SbaaT, abcd, 1.0, 0}, {SbaaT, abdc, -1.0, 0}})) != hipSuccess) return e;
+      if ((e = pack(3, 1, 0, {{DaaT, abcd, 1.0, 0}})) != hipSuccess) return e;
+      if ((e = pack(4, 0, 0, {{Sbaa, abcd, 1.0, 0}, {Sbaa, abdc, -1.0, 0}})) != hipSuccess) return e;
+      return pack(5, 1, 0, {{G2aaT, abcd, 1.0, 0}});
+    };
     const int R2 = (int)r2;
     double *Gp = T4, *Gm = T4 + (int64_t)nle * nle;  // Gb_ab +- (rows packed)
     // Below kAbPackMinR the packing passes and the second launch cost more than
@@ -989,13 +1011,7 @@ extern "C" acse_status acse_residual_vjp(acse_ctx ctx, const acse_problem *prob,
     if (!pack_ab) {
       const int Akl_ij[4] = {2, 3, 0, 1};   // Sb[i,j,k,l] as rows (k,l), cols (i,j)
       const int Brs_kl[4] = {2, 3, 0, 1};   // X[k,l,r,s] as rows (r,s), cols (k,l)
-      HIP_TRY(ctx, pack(0, 1, 0, {{Sbaa, abcd, 1.0, 0}, {Sbaa, bacd, -1.0, 0}, {Sbaa, abdc, -1.0, 0},
-                                  {Sbaa, badc, 1.0, 0}}));
-      HIP_TRY(ctx, pack(1, 1, 0, {{w.Aaa, cdab, 1.0, 0}, {w.G2aa, cdab, -1.0, 0}}));
-      HIP_TRY(ctx, pack(2, 0, 0, {{Sbaa, cdab, 1.0, 0}, {Sbaa, dcab, -1.0, 0}}));
-      HIP_TRY(ctx, pack(3, 1, 0, {{prob->d2aa, cdab, 1.0, 0}}));
-      HIP_TRY(ctx, pack(4, 0, 0, {{Sbaa, abcd, 1.0, 0}, {Sbaa, abdc, -1.0, 0}}));
-      HIP_TRY(ctx, pack(5, 1, 0, {{w.G2aa, cdab, 1.0, 0}}));
+      HIP_TRY(ctx, pack_aa());
       HIP_TRY(ctx, permute(prec, vop(6), true, Sbab, ID, 1.0, nullptr, ID, 0.0, 0));
       HIP_TRY(ctx, permute(prec, vop(7), true, Sbab, Akl_ij, 1.0, nullptr, ID, 0.0, 0));
       HIP_TRY(ctx, permute(prec, vop(8), true, w.Aab, Brs_kl, 1.0, w.G2ab, Brs_kl, -1.0, 0));
@@ -1015,21 +1031,15 @@ extern "C" acse_status acse_residual_vjp(acse_ctx ctx, const acse_problem *prob,
       HIP_TRY(ctx, launch_unpack_pairs(r, 0, T3, nlt, Maa, s));
     }
     if (pack_ab) {
-      HIP_TRY(ctx, pack(0, 1, 0, {{Sbaa, abcd, 1.0, 0}, {Sbaa, bacd, -1.0, 0}, {Sbaa, abdc, -1.0, 0},
-                                  {Sbaa, badc, 1.0, 0}}));
-      HIP_TRY(ctx, pack(1, 1, 0, {{w.Aaa, cdab, 1.0, 0}, {w.G2aa, cdab, -1.0, 0}}));
-      HIP_TRY(ctx, pack(2, 0, 0, {{Sbaa, cdab, 1.0, 0}, {Sbaa, dcab, -1.0, 0}}));
-      HIP_TRY(ctx, pack(3, 1, 0, {{prob->d2aa, cdab, 1.0, 0}}));
-      HIP_TRY(ctx, pack(4, 0, 0, {{Sbaa, abcd, 1.0, 0}, {Sbaa, abdc, -1.0, 0}}));
-      HIP_TRY(ctx, pack(5, 1, 0, {{w.G2aa, cdab, 1.0, 0}}));
+      HIP_TRY(ctx, pack_aa());
       HIP_TRY(ctx, pack(6, 2, 1, {{Sbab, abcd, 0.5, 0}, {Sbab, badc, 0.5, 0}, {Sbab, abdc, 0.5, 1},
                                   {Sbab, bacd, 0.5, 1}}));
-      HIP_TRY(ctx, pack(7, 2, 1, {{w.Aab, cdab, 1.0, 0}, {w.Aab, cdba, 1.0, 0}, {w.G2ab, cdab, -1.0, 0},
-                                  {w.G2ab, cdba, -1.0, 0}}));
+      double *BabT = Gbab;
+      HIP_TRY(ctx, exch(BabT, w.Aab, w.G2ab, -1.0));
+      HIP_TRY(ctx, pack(7, 2, 1, {{BabT, abcd, 1.0, 0}, {BabT, bacd, 1.0, 0}}));
       HIP_TRY(ctx, pack(8, 1, 0, {{Sbab, abcd, 0.5, 0}, {Sbab, badc, 0.5, 0}, {Sbab, abdc, -0.5, 0},
                                   {Sbab, bacd, -0.5, 0}}));
-      HIP_TRY(ctx, pack(9, 1, 0, {{w.Aab, cdab, 1.0, 0}, {w.Aab, cdba, -1.0, 0}, {w.G2ab, cdab, -1.0, 0},
-                                  {w.G2ab, cdba, 1.0, 0}}));
+      HIP_TRY(ctx, pack(9, 1, 0, {{BabT, abcd, 1.0, 0}, {BabT, bacd, -1.0, 0}}));
       GemmBatch b{};
       b.count = 5;
       pair_set(b, 0, 0, 1, 0.5, T1, nlt, nlt, 0);
@@ -1045,14 +1055,18 @@ extern "C" acse_status acse_residual_vjp(acse_ctx ctx, const acse_problem *prob,
     }
     if (pack_ab) {
       double *Bp = T1, *Bm = T1 + (int64_t)r2 * nle, *Mp = T2, *Mm = T2 + (int64_t)r2 * nle;
-      HIP_TRY(ctx, pack(0, 0, 1, {{Sbab, cdab, 1.0, 0}, {Sbab, dcab, 1.0, 1}}));
-      HIP_TRY(ctx, pack(1, 2, 1, {{prob->d2ab, cdab, 1.0, 0}, {prob->d2ab, cdba, 1.0, 0}}));
-      HIP_TRY(ctx, pack(2, 0, 0, {{Sbab, cdab, 1.0, 0}, {Sbab, dcab, -1.0, 0}}));
-      HIP_TRY(ctx, pack(3, 1, 0, {{prob->d2ab, cdab, 1.0, 0}, {prob->d2ab, cdba, -1.0, 0}}));
+      double *SbabT = T3, *DabT = T4, *G2abT = Vraw;
+      HIP_TRY(ctx, exch(SbabT, Sbab, nullptr, 0.0));
+      HIP_TRY(ctx, exch(DabT, prob->d2ab, nullptr, 0.0));
+      HIP_TRY(ctx, exch(G2abT, w.G2ab, nullptr, 0.0));
+      HIP_TRY(ctx, pack(0, 0, 1, {{SbabT, abcd, 1.0, 0}, {SbabT, abdc, 1.0, 1}}));
+      HIP_TRY(ctx, pack(1, 2, 1, {{DabT, abcd, 1.0, 0}, {DabT, bacd, 1.0, 0}}));
+      HIP_TRY(ctx, pack(2, 0, 0, {{SbabT, abcd, 1.0, 0}, {SbabT, abdc, -1.0, 0}}));
+      HIP_TRY(ctx, pack(3, 1, 0, {{DabT, abcd, 1.0, 0}, {DabT, bacd, -1.0, 0}}));
       HIP_TRY(ctx, pack(4, 0, 1, {{Sbab, abcd, 1.0, 0}, {Sbab, abdc, 1.0, 1}}));
-      HIP_TRY(ctx, pack(5, 2, 1, {{w.G2ab, cdab, 1.0, 0}, {w.G2ab, cdba, 1.0, 0}}));
+      HIP_TRY(ctx, pack(5, 2, 1, {{G2abT, abcd, 1.0, 0}, {G2abT, bacd, 1.0, 0}}));
       HIP_TRY(ctx, pack(6, 0, 0, {{Sbab, abcd, 1.0, 0}, {Sbab, abdc, -1.0, 0}}));
-      HIP_TRY(ctx, pack(7, 1, 0, {{w.G2ab, cdab, 1.0, 0}, {w.G2ab, cdba, -1.0, 0}}));
+      HIP_TRY(ctx, pack(7, 1, 0, {{G2abT, abcd, 1.0, 0}, {G2abT, bacd, -1.0, 0}}));
       GemmBatch b{};
       b.count = 4;
       pair_set(b, 0, 0, 1, 4.0, Bp, R2, nle, 1);  // 2 Gamma2_ab = 4 d2ab
