@@ -154,3 +154,26 @@ def test_solve_rejects_bad_options(acse, ctx, bad, match):
     with pytest.raises(acse.AcseError, match=match):
         ctx.solve(p["h"], p["V"], p["gamma"], p["d2aa"], p["d2ab"], p["N"] // 2, **kw)
     assert np.array_equal(before, p["d2aa"])
+
+
+@pytest.mark.parametrize("precision,tol", [("fp32", 1e-5), ("bf16x3", 5e-5)])
+def test_solve_mixed_precision(ctx, precision, tol):
+    """The iteration with the contractions in FP32 / split BF16 (step, trace
+    restoration, energy and the decisions in FP64): the same decisions as the
+    FP64 oracle (margins checked) and results within the precision's bar."""
+    p = PROBLEMS["r10"]()
+    print(f"[solve] r10 fixed {precision}", flush=True)
+    o = sv.euler(p["h"], p["V"], p["N"], p["gamma"], p["d2aa"], p["d2ab"], eps=1e-3, de_tol=1e-9,
+                 max_iter=3, control=sv.FIXED)
+    assert margins_ok(o, 1e-3)
+    g = ctx.solve(p["h"], p["V"], p["gamma"], p["d2aa"], p["d2ab"], p["N"] // 2, eps=1e-3, de_tol=1e-9,
+                  max_iter=3, control="fixed", precision=precision)
+    assert g["stop"] == STOPS[o["stop"]] and g["iterations"] == o["iterations"]
+    assert len(g["trials"]) == len(o["trials"])
+    for (ge, gE, gf, gn, ga), (oe, oE, of, on, oa) in zip(g["trials"], o["trials"]):
+        assert gn == on and ga == oa and ge == oe
+        assert abs(gE - oE) <= tol * abs(oE - o["energy0"])
+        assert abs(gf - of) <= tol * of
+    for key in ("d2aa", "d2ab"):
+        x = g[key].cpu().numpy()
+        assert np.abs(x - o[key]).max() <= tol * np.abs(o[key]).max(), key
