@@ -295,6 +295,67 @@ class Context:
                     trial_count=res.trials, maps=res.maps, stop=STOP_REASONS[res.stop],
                     trials=[(q.eps, q.energy, q.norm2, q.step, bool(q.accepted)) for q in hist])
 
+    def solve_checkpointed(self, h, V, d1, d2aa, d2ab, n_alpha, path, every=10, max_iter=100, eps=1e-3,
+                           **kw):
+        """The iteration of ``solve`` in chunks of ``every`` steps.  After each
+        chunk the state (1-RDM, 2-RDM blocks, the next step size, the steps
+        taken, the lambda trajectory) is written to ``path`` (numpy .npz of
+        plain arrays, replaced atomically).  If ``path`` exists the iteration
+        resumes from it: the state it holds replaces d1, d2aa and d2ab, and it
+        must have been written for the same h, V and electron count.  Each chunk
+        starts from the state the previous one returned, so the result is the
+        one an uninterrupted ``solve`` reaches.  Returns the dict of the last
+        chunk with ``iterations`` counting every chunk's steps, ``trajectory``
+        (see ``trajectory``) and ``resumed``."""
+        import hashlib
+        import numpy as np
+
+        tag = hashlib.sha256()
+        for x in (h, V):
+            tag.update(np.ascontiguousarray(_host64(x)).tobytes())
+        tag.update(str(int(n_alpha)).encode())
+        tag = tag.hexdigest()
+        done, resumed = 0, False
+        traj = None
+        if os.path.exists(path):
+            with np.load(path, allow_pickle=False) as z:
+                if str(z["tag"]) != tag:
+                    raise ValueError(f"{path} was written for another problem")
+                d1, d2aa, d2ab = z["d1"], z["d2aa"], z["d2ab"]
+                eps = float(z["eps"])
+                done = int(z["iterations"])
+                traj = [tuple(row) for row in z["trajectory"]]
+                stop = str(z["stop"])
+            resumed = True
+            if stop != "max_iter" or done >= max_iter:
+                return dict(d1=d1, d2aa=d2aa, d2ab=d2ab, iterations=done, trajectory=traj, stop=stop,
+                            resumed=True)
+        out = None
+        while done < max_iter:
+            n = min(int(every), max_iter - done)
+            out = self.solve(h, V, d1, d2aa, d2ab, n_alpha, eps=eps, max_iter=n, **kw)
+            part = trajectory(out)
+            if traj is None:
+                traj = part
+            else:
+                lam0 = traj[-1][0]
+                traj += [(lam0 + lam, e, lg) for lam, e, lg in part[1:]]
+            done += out["iterations"]
+            d1, d2aa, d2ab = out["d1"], out["d2aa"], out["d2ab"]
+            if out["iterations"]:
+                eps = out["eps"]
+            tmp = path + ".tmp.npz"
+            np.savez(tmp, tag=np.array(tag), d1=_host64(d1), d2aa=_host64(d2aa), d2ab=_host64(d2ab),
+                     eps=np.array(eps), iterations=np.array(done), stop=np.array(out["stop"]),
+                     trajectory=np.array(traj, dtype=np.float64).reshape(-1, 3))
+            os.replace(tmp, path)
+            if out["stop"] != "max_iter":
+                break
+        if out is None:
+            return dict(d1=d1, d2aa=d2aa, d2ab=d2ab, iterations=done, trajectory=traj, stop="max_iter",
+                        resumed=resumed)
+        return dict(out, iterations=done, trajectory=traj, resumed=resumed)
+
     def residual_vjp_raw(self, prob, opts, Rbar_aa, Rbar_ab, h_bar, V_bar, d1_bar, d2aa_bar, d2ab_bar):
         self._check(_lib.acse_residual_vjp(self._h, ctypes.byref(prob), ctypes.byref(opts),
                                            _ptr(Rbar_aa), _ptr(Rbar_ab), _ptr(h_bar), _ptr(V_bar),
@@ -405,6 +466,27 @@ class ACSEEnergy(torch.autograd.Function):
         h, V, d2aa, d2ab = fctx.saved_tensors
         g = ctx.energy_vjp(h, V, d2aa, d2ab, n_alpha, float(Eb))
         return (None,) + tuple(x.to(t.dtype) for x, t in zip(g, (h, V, d2aa, d2ab))) + (None,)
+
+
+def _host64(x):
+    import numpy as np
+    if isinstance(x, torch.Tensor):
+        return x.detach().to("cpu", torch.float64).numpy()
+    return np.asarray(x, dtype=np.float64)
+
+
+def trajectory(result):
+    """The trajectory the method section plots, from a ``solve`` result: a
+    list of (lambda, E, log10 ||R||) for the input state and each accepted step,
+    lambda being the sum of the accepted step sizes (eps n at a fixed eps)."""
+    import math
+    out = [(0.0, result["energy0"], 0.5 * math.log10(result["norm2_0"]) if result["norm2_0"] > 0 else -math.inf)]
+    lam = 0.0
+    for eps, e, n2, _step, accepted in result["trials"]:
+        if accepted:
+            lam += eps
+            out.append((lam, e, 0.5 * math.log10(n2) if n2 > 0 else -math.inf))
+    return out
 
 
 def status_str(code):

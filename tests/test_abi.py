@@ -95,3 +95,15 @@ def test_struct_layouts_match_header(tmp_path):
         assert int(out[st]) == ctypes.sizeof(cls), st
         for f, _ in cls._fields_:
             assert int(out[f"{st}.{f}"]) == getattr(cls, f).offset, (st, f)
+
+
+def test_trajectory_from_trials():
+    """lambda = sum of the accepted step sizes; E and log10 ||R|| of the input
+    state and of each accepted trial (rejected trials are skipped)."""
+    import math
+    import paper_2604_02550_amd as acse
+    res = dict(energy0=-1.0, norm2_0=100.0,
+               trials=[(0.1, -2.0, 50.0, 0, False), (0.05, -1.5, 81.0, 0, True),
+                       (0.05, -1.8, 64.0, 1, True)])
+    t = acse.trajectory(res)
+    assert t == [(0.0, -1.0, 1.0), (0.05, -1.5, math.log10(9.0)), (0.1, -1.8, math.log10(8.0))]

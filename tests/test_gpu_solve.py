@@ -177,3 +177,31 @@ def test_solve_mixed_precision(ctx, precision, tol):
     for key in ("d2aa", "d2ab"):
         x = g[key].cpu().numpy()
         assert np.abs(x - o[key]).max() <= tol * np.abs(o[key]).max(), key
+
+
+def test_solve_checkpoint_resume(acse, ctx, tmp_path):
+    """The chunked iteration with a checkpoint file reaches the state of one
+    uninterrupted call, also when it is stopped after a chunk and resumed from
+    the file; the trajectory is lambda = eps n at a fixed eps."""
+    p = PROBLEMS["r6"]()
+    args = (p["h"], p["V"], p["gamma"], p["d2aa"], p["d2ab"], p["N"] // 2)
+    full = ctx.solve(*args, eps=1e-3, de_tol=0.0, max_iter=4)
+    assert full["iterations"] == 4
+    path = str(tmp_path / "acse_state.npz")
+    first = ctx.solve_checkpointed(*args, path=path, every=1, max_iter=2, eps=1e-3, de_tol=0.0)
+    assert first["iterations"] == 2 and not first["resumed"]
+    rest = ctx.solve_checkpointed(*args, path=path, every=1, max_iter=4, eps=1e-3, de_tol=0.0)
+    assert rest["resumed"] and rest["iterations"] == 4
+    for key in ("d2aa", "d2ab", "d1"):
+        a = full[key].cpu().numpy()
+        b = rest[key].cpu().numpy()
+        assert np.abs(a - b).max() <= 1e-14 * np.abs(a).max(), key
+    traj = rest["trajectory"]
+    ref = acse.trajectory(full)
+    assert len(traj) == len(ref) == 5
+    for (l1, e1, g1), (l2, e2, g2) in zip(traj, ref):
+        assert abs(l1 - l2) <= 1e-15 and abs(e1 - e2) <= 1e-12 * abs(e2) and abs(g1 - g2) <= 1e-12
+    assert [round(t[0] / 1e-3) for t in traj] == [0, 1, 2, 3, 4]
+    # a file written for another Hamiltonian is refused
+    with pytest.raises(ValueError, match="another problem"):
+        ctx.solve_checkpointed(p["h"] * 1.01, *args[1:], path=path, every=1, max_iter=6, eps=1e-3)
