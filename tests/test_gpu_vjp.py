@@ -155,6 +155,39 @@ def test_residual_vjp_r30_finite_difference(ctx, vjp30, precision, tol):
         assert abs(an - fd[k]) <= tol * scale, (k, an, fd[k])
 
 
+@pytest.mark.parametrize("precision,tol", [("fp64", 1e-7), ("fp32", 1e-4)])
+def test_residual_vjp_r44_finite_difference(acse, precision, tol):
+    """At r = 44 the alpha-beta pp adjoint products run packed (as from r = 40
+    on): <gradient, direction> against central finite differences of
+    <Rbar, R> along one structured direction per input, with R from the FP64
+    residual on the GPU (itself checked against the oracle elsewhere)."""
+    import torch
+    p = gen.problem(44, 26, 88, seed=44)
+    rng = np.random.default_rng(44)
+    Rb = gen.cotangent(rng, p["r"])
+    dirs = gen.symmetric_direction(rng, p["r"])
+    ctx = acse.Context(r_max=p["r"])
+    try:
+        dev = ctx.device
+        Rbt = [torch.as_tensor(a, device=dev) for a in Rb]
+
+        def loss(**over):
+            q = {k: over.get(k, p[k]) for k in KEYS}
+            Raa, Rab, _ = ctx.residual(q["h"], q["V"], q["gamma"], q["d2aa"], q["d2ab"], p["N"] // 2)
+            return float((Rbt[0] * Raa).sum() + (Rbt[1] * Rab).sum())
+
+        got = gpu_vjp(ctx, p, Rb, precision)
+        t = 1e-5
+        for k in KEYS:
+            fd = (loss(**{k: p[k] + t * dirs[k]}) - loss(**{k: p[k] - t * dirs[k]})) / (2 * t)
+            an = float(np.sum(got[k] * dirs[k]))
+            scale = max(abs(fd), np.linalg.norm(got[k]))
+            print(f"[vjp44 {precision}] {k} fd {fd:.10e} an {an:.10e}", flush=True)
+            assert abs(an - fd) <= tol * scale, (k, an, fd)
+    finally:
+        ctx.close()
+
+
 def test_autograd_function_and_determinism(acse, ctx):
     import torch
     p = PROBLEMS["r10"]()
