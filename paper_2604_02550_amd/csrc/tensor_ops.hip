@@ -1184,8 +1184,15 @@ k_finish(int r, double sigma, const double *__restrict__ Saa, const double *__re
 __global__ void __launch_bounds__(256)
 k_reduce_sum(int64_t n, const double *__restrict__ part, double *__restrict__ out) {
   __shared__ double red[256];
-  double acc = 0.0;
-  for (int64_t q = threadIdx.x; q < n; q += 256) acc += part[q];
+  // eight independent partial sums per thread keep eight loads in flight
+  double a[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+  int64_t q = threadIdx.x;
+  for (; q + 7 * 256 < n; q += 8 * 256) {
+#pragma unroll
+    for (int u = 0; u < 8; ++u) a[u] += part[q + u * 256];
+  }
+  for (; q < n; q += 256) a[0] += part[q];
+  const double acc = ((a[0] + a[1]) + (a[2] + a[3])) + ((a[4] + a[5]) + (a[6] + a[7]));
   red[threadIdx.x] = acc;
   __syncthreads();
   for (int w = 128; w > 0; w >>= 1) {
@@ -1509,19 +1516,23 @@ k_contract_1rdm(int r, double two_over_nm1, const double *__restrict__ d2aa,
 //   d2 <- (d2 + eps U) * (Tr_in / Tr_new) per block, in place, and the energy
 //   partials 2 K_s (d2aa + d2ab) of the updated blocks.  The updated element is
 //   fma(eps, U, d2) in both kernels, so the trace matches the update exactly.
+// Traces of 2D and of 2D + eps U per block (diagonal elements (p,q,p,q), one
+// per thread and 256 per block): partials part[4 b + k], k = Tr d2aa, Tr d2ab,
+// Tr (d2aa + eps U_aa), Tr (d2ab + eps U_ab); then summed in block order.
 __global__ void __launch_bounds__(256)
 k_step_traces(int r, double eps, const double *__restrict__ d2aa, const double *__restrict__ d2ab,
               const double *__restrict__ Uaa, const double *__restrict__ Uab,
-              double *__restrict__ traces) {
+              double *__restrict__ part) {
   __shared__ double red[4][256];
   const int64_t r2 = (int64_t)r * r;
+  const int64_t q = (int64_t)blockIdx.x * 256 + threadIdx.x;
   double a = 0.0, b = 0.0, na = 0.0, nb = 0.0;
-  for (int64_t q = threadIdx.x; q < r2; q += 256) {
+  if (q < r2) {
     const int64_t d = q * r2 + q;  // element (p,q,p,q) at row = col = p*r+q
-    a += d2aa[d];
-    b += d2ab[d];
-    na += fma(eps, Uaa[d], d2aa[d]);
-    nb += fma(eps, Uab[d], d2ab[d]);
+    a = d2aa[d];
+    b = d2ab[d];
+    na = fma(eps, Uaa[d], a);
+    nb = fma(eps, Uab[d], b);
   }
   red[0][threadIdx.x] = a;
   red[1][threadIdx.x] = b;
@@ -1533,7 +1544,15 @@ k_step_traces(int r, double eps, const double *__restrict__ d2aa, const double *
       for (int k = 0; k < 4; ++k) red[k][threadIdx.x] += red[k][threadIdx.x + w];
     __syncthreads();
   }
-  if (threadIdx.x < 4) traces[threadIdx.x] = red[threadIdx.x][0];
+  if (threadIdx.x < 4) part[4 * blockIdx.x + threadIdx.x] = red[threadIdx.x][0];
+}
+
+__global__ void k_step_traces_sum(int nblk, const double *__restrict__ part, double *__restrict__ traces) {
+  const int k = threadIdx.x;
+  if (k >= 4) return;
+  double t = 0.0;
+  for (int b = 0; b < nblk; ++b) t += part[4 * b + k];
+  traces[k] = t;
 }
 
 __global__ void __launch_bounds__(256)
@@ -1967,7 +1986,12 @@ hipError_t launch_step_tail(int r, int N, double eps, const double *h, const dou
                             double *traces, double *partial, double *E_out, hipStream_t s) {
   const int64_t n4 = (int64_t)r * r * r * r;
   const int64_t nb = (n4 + 255) / 256;
-  hipLaunchKernelGGL(k_step_traces, dim3(1), dim3(256), 0, s, r, eps, d2aa, d2ab, Uaa, Uab, traces);
+  // trace partials in `partial` (4 per 256 diagonal elements, at most 144 at
+  // r = 96; the buffer holds at least 32 and r^4/256 doubles), then the energy
+  // partials of the update
+  const int nbt = (int)(((int64_t)r * r + 255) / 256);
+  hipLaunchKernelGGL(k_step_traces, dim3((unsigned)nbt), dim3(256), 0, s, r, eps, d2aa, d2ab, Uaa, Uab, partial);
+  hipLaunchKernelGGL(k_step_traces_sum, dim3(1), dim3(64), 0, s, nbt, partial, traces);
   hipLaunchKernelGGL(k_step_update, dim3((unsigned)nb), dim3(256), 0, s, r, eps, 1.0 / (N - 1), traces,
                      h, V, Uaa, Uab, d2aa, d2ab, partial);
   hipLaunchKernelGGL(k_reduce_sum, dim3(1), dim3(256), 0, s, nb, partial, E_out);
