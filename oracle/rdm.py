@@ -151,3 +151,53 @@ def gamma3_valdemoro_wform(g1, g2):
     return (e('ad,bcef->abcdef', g1, w) - e('ae,bcdf->abcdef', g1, w) + e('af,bcde->abcdef', g1, w)
             - e('bd,acef->abcdef', g1, w) + e('be,acdf->abcdef', g1, w) - e('bf,acde->abcdef', g1, w)
             + e('cd,abef->abcdef', g1, w) - e('ce,abdf->abcdef', g1, w) + e('cf,abde->abcdef', g1, w))
+
+
+# ---------------------------------------------------------------------------
+# Nakatsuji-Yasuda approximation to the 3-cumulant (Eq. (8); App. D, NY part)
+# ---------------------------------------------------------------------------
+
+def sigma_spin_orbital(sigma):
+    """Spin-orbital weights from the spatial ones (both spins of an orbital
+    share its Hartree-Fock occupation): +1 occupied, -1 unoccupied."""
+    s = np.asarray(sigma, dtype=np.float64)
+    return np.concatenate([s, s])
+
+
+def _perm_sign(p):
+    p = list(p)
+    sign = 1.0
+    for i in range(len(p)):
+        while p[i] != i:
+            j = p[i]
+            p[i], p[j] = p[j], p[i]
+            sign = -sign
+    return sign
+
+
+def d3_ny_cumulant(d1, d2, sigma_so):
+    """3Delta^{ijp}_{rql} = 1/6 sum_a sigma_a A[ 2Delta^{ia}_{rq} 2Delta^{jp}_{al} ]
+    (Eq. (8)), A the sum over all signed permutations of the upper indices
+    (i, j, p) and, independently, of the lower ones (r, q, l) -- 36 terms, a
+    unit weight each, as the explicit expansion of the NY appendix lists them;
+    a stays fixed.  2Delta is the cumulant of Eq. (7) in the normalisation of
+    Eq. (6), so that 3D = 3D_V + 3Delta.
+
+    The plain definition, materialised with axes [i, j, p, r, q, l]: n^6
+    memory, small n only.  Pinned against the exact 3-cumulant of a
+    determinant with a small doubles admixture, which it matches through
+    second order.
+    """
+    c2 = cumulant2(d1, d2)
+    prod = np.einsum('a,iarq,jpal->ijprql', np.asarray(sigma_so, dtype=np.float64), c2, c2)
+    out = np.zeros_like(prod)
+    import itertools
+    for up in itertools.permutations(range(3)):
+        for lo in itertools.permutations(range(3)):
+            out += _perm_sign(up) * _perm_sign(lo) * prod.transpose(list(up) + [3 + x for x in lo])
+    return out / 6.0
+
+
+def d3_ny(d1, d2, sigma_so):
+    """NY 3-RDM: the Valdemoro terms of Eq. (7) plus the NY 3-cumulant."""
+    return d3_valdemoro(d1, d2) + d3_ny_cumulant(d1, d2, sigma_so)

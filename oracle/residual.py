@@ -109,18 +109,56 @@ def contraction_b(X, d1, d2):
     return 6.0 * bt
 
 
-def residual_map(X, d1, d2, hermitian):
+def contraction_b_ny(X, d1, d2, sigma_so):
+    """The NY cumulant's share of B: 6 sum_pqr X^{kp}_{rq} 3Delta^{ijp}_{rql}
+    with the 3Delta of Eq. (8), never formed.
+
+    Collapsing the 36 signed permutations with the pair antisymmetry of
+    2Delta leaves 9 distinct products, each with weight 4: the upper index x
+    of the first cumulant is i (+), j (-) or p (+, the second then carrying
+    (i, j)); the lower index y of the second cumulant is l (+), r (-) or q (-),
+    the first carrying the other two in their order.  Each product is two
+    pairwise contractions with n^4 intermediates (n^6 work), summed over the
+    orbital a with weight sigma_a.  The x = j products are the x = i ones with
+    i and j exchanged.  Axes [i,j,k,l].  Torch float64 (differentiable).
+    """
+    X, d1, d2 = _t(X), _t(d1), _t(d2)
+    s = _t(sigma_so)
+    c2 = d2 - 0.5 * (torch.einsum('ir,jq->ijrq', d1, d1) - torch.einsum('jr,iq->ijrq', d1, d1))
+    cs = c2 * s[None, None, :, None]          # sigma_a on the first lower index: 2Delta^{..}_{a.}
+    e = torch.einsum
+    # y = l: first cumulant lower (r, q), second (a, l)
+    t_il = e('kpia,jpal->ijkl', e('kprq,iarq->kpia', X, c2), cs)
+    t_pl = e('ka,ijal->ijkl', e('kprq,parq->ka', X, c2), cs)
+    # y = r: first cumulant lower (l, q), second (a, r)
+    t_ir = e('kqja,ialq->ijkl', e('kprq,jpar->kqja', X, cs), c2)
+    t_pr = e('kral,ijar->ijkl', e('kprq,palq->kral', X, c2), cs)
+    # y = q: first cumulant lower (r, l), second (a, q)
+    t_iq = e('krja,iarl->ijkl', e('kprq,jpaq->krja', X, cs), c2)
+    t_pq = e('kqal,ijaq->ijkl', e('kprq,parl->kqal', X, c2), cs)
+
+    def sw(t):
+        return t - t.permute(1, 0, 2, 3)
+    return 4.0 * (sw(t_il) + t_pl - sw(t_ir) - t_pr - sw(t_iq) - t_pq)
+
+
+def residual_map(X, d1, d2, hermitian, sigma_so=None):
     """F(X) via Eqs. (B8)-(B9) with the factorised B (tier B).
 
     A^{ij}_{kl} = 2 sum_qp X^{kl}_{qp} 2D^{ij}_{qp};  C = B - B(k<->l);
     Hermitian X:       F = A - A' - C + C'
     anti-Hermitian X:  F = A + A' - C - C'      (' : exchange (ij)<->(kl)).
+    With sigma_so (spin-orbital HF occupations, +1 / -1) the 3-RDM is the NY
+    one, 3D_V + 3Delta_NY (Eq. (8)); F is linear in 3D, so B gains the
+    cumulant's share.
     """
     X, d1, d2 = _t(X), _t(d1), _t(d2)
     n = d1.shape[0]
     n2 = n * n
     A = 2.0 * (d2.reshape(n2, n2) @ X.reshape(n2, n2).T).reshape(n, n, n, n)
     B = contraction_b(X, d1, d2)
+    if sigma_so is not None:
+        B = B + contraction_b_ny(X, d1, d2, sigma_so)
     C = B - B.permute(0, 1, 3, 2)
     del B
     At = A.permute(2, 3, 0, 1)

@@ -17,6 +17,9 @@ Readings:
   arithmetic, so each block is rescaled to its input trace (removes rounding
   drift only).
 * 1-RDM after the step: the contraction 1D = 2/(N-1) sum_q 2D[p,q,r,q].
+* Reconstruction: ``sigma`` None is the Valdemoro 3-RDM; a per-spatial-orbital
+  array of +1 (occupied in the Hartree-Fock reference) / -1 selects the NY one
+  (Eq. (8)) for both maps of the step.
 """
 import numpy as np
 import torch
@@ -47,25 +50,30 @@ def energy(h, V, N, d2aa, d2ab):
     return float(np.sum(K * d2))
 
 
-def residual(h, V, N, gamma, d2aa, d2ab):
+def _sigma_so(sigma):
+    return None if sigma is None else rdm.sigma_spin_orbital(sigma)
+
+
+def residual(h, V, N, gamma, d2aa, d2ab, sigma=None):
     """R = F(K) (Eq. (4)); returns (R_aa, R_ab, ||R||^2 over spin orbitals)."""
     K = rdm.reduced_hamiltonian(h, V, N)
     d1, d2 = rdm.blocks_to_spin_orbital(gamma, d2aa, d2ab)
-    R = residual_map(K, d1, d2, hermitian=True).numpy()
+    R = residual_map(K, d1, d2, hermitian=True, sigma_so=_sigma_so(sigma)).numpy()
     raa, rab = rdm.spin_orbital_to_blocks(R)
     return raa, rab, norm2_spin_orbital(R)
 
 
-def step(h, V, N, gamma, d2aa, d2ab, eps, active=None, keep_spin_orbital=False):
+def step(h, V, N, gamma, d2aa, d2ab, eps, active=None, keep_spin_orbital=False, sigma=None):
     """One Euler step (Eq. (9)).  Returns a dict of blocks and scalars."""
     r = h.shape[0]
     K = rdm.reduced_hamiltonian(h, V, N)
     d1, d2 = rdm.blocks_to_spin_orbital(gamma, d2aa, d2ab)
-    R = residual_map(K, d1, d2, hermitian=True).numpy()
+    sso = _sigma_so(sigma)
+    R = residual_map(K, d1, d2, hermitian=True, sigma_so=sso).numpy()
     n2 = norm2_spin_orbital(R)
     mask = active_mask(active, r)
     Rm = R if mask is None else R * mask
-    U = residual_map(Rm, d1, d2, hermitian=False).numpy()
+    U = residual_map(Rm, d1, d2, hermitian=False, sigma_so=sso).numpy()
     raa, rab = rdm.spin_orbital_to_blocks(R)
     uaa, uab = rdm.spin_orbital_to_blocks(U)
     d2aa_1 = d2aa + eps * uaa
