@@ -101,7 +101,25 @@ typedef struct {
                              option of the method section); the norm is taken first. */
   int32_t tile;           /* GEMM tile configuration, -1 = autotuned default */
   int32_t flags;          /* bitwise OR of ACSE_FLAG_* (0 = none) */
+  int32_t reconstruction; /* acse_reconstruction of the 3-RDM (0 = Valdemoro) */
+  const int8_t *ny_sigma; /* HOST [r] or NULL, ACSE_RECON_NY only: +1 for an orbital occupied
+                             in the Hartree-Fock reference, -1 for an unoccupied one;
+                             NULL = orbitals 0 .. n_alpha-1 occupied.  Other values are an
+                             ACSE_ERR_ARG. */
 } acse_options;
+
+/* 3-RDM reconstruction of the residual map (Eq. (7)).
+ *   ACSE_RECON_V   Valdemoro: the 3-cumulant is dropped (App. C, Eq. (C5)).
+ *   ACSE_RECON_NY  Nakatsuji-Yasuda: the 3-cumulant is approximated by the
+ *                  sigma-weighted, antisymmetrised product of two 2-cumulants
+ *                  of Eq. (8) (App. D, NY part), never formed.  Both maps of
+ *                  a step use it.  Its share runs as 30 spatial-block FP64
+ *                  GEMMs of r^2 x r^2 x r^2 per map (a spin-orbital contraction
+ *                  split over the spins of its internal indices), so it is
+ *                  FP64 only: another precision is ACSE_ERR_UNSUPPORTED, as are
+ *                  the adjoint (acse_residual_vjp), the quadratic step control
+ *                  of acse_solve (which needs it) and the batched residual. */
+typedef enum { ACSE_RECON_V = 0, ACSE_RECON_NY = 1 } acse_reconstruction;
 
 /* acse_options.flags: run the general-size kernels at every r (the one-index
  * transforms for the ph A operands (otherwise r > 56); the G2 kernel that
@@ -280,10 +298,12 @@ acse_status acse_energy_vjp(acse_ctx ctx, const acse_problem *prob, double Ebar,
  *   3  grouped pair-index GEMM (the six O(r^6) contractions of one map)
  *   4  assembly, (ij)<->(kl) exchange and the FP64 norm
  *   5  step tail: axpy, trace restoration, 1-RDM contraction, energy
+ *   6  Nakatsuji-Yasuda share (cumulant blocks, operand layouts, its GEMMs
+ *      and the combination into the map; ACSE_RECON_NY only)
  * acse_profile_enable(ctx, 1) clears the totals and starts recording;
  * acse_profile_read synchronises the stream and returns the totals (ms and
  * number of timed intervals per stage) since the last enable. */
-#define ACSE_NUM_STAGES 6
+#define ACSE_NUM_STAGES 7
 typedef struct {
   double ms[ACSE_NUM_STAGES];
   int64_t count[ACSE_NUM_STAGES];

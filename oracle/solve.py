@@ -46,9 +46,9 @@ FIXED, BACKTRACK, QUADRATIC = 0, 1, 2
 STOP_MAX_ITER, STOP_CONVERGED, STOP_ENERGY_ROSE, STOP_NORM_ROSE = 0, 1, 2, 3
 
 
-def _residual(K, gamma, d2aa, d2ab):
+def _residual(K, gamma, d2aa, d2ab, sigma_so=None):
     d1, d2 = rdm.blocks_to_spin_orbital(gamma, d2aa, d2ab)
-    R = residual_map(K, d1, d2, hermitian=True).numpy()
+    R = residual_map(K, d1, d2, hermitian=True, sigma_so=sigma_so).numpy()
     return R, float(np.sum(R ** 2)), d1, d2
 
 
@@ -93,11 +93,16 @@ def quadratic_trial_step(f0, g0, eps, f_eps, eps_max):
 
 
 def euler(h, V, N, gamma, d2aa, d2ab, eps=1e-3, de_tol=1e-6, max_iter=100, control=FIXED,
-          max_halvings=8, eps_max=0.0, active=None):
+          max_halvings=8, eps_max=0.0, active=None, sigma=None):
     """Run the iteration; returns a dict with the final gamma, d2aa, d2ab, the
     energies and norms of the input and returned states, the stop reason, the
     accepted-step count and the list of trials (eps, E, ||R||^2, step index,
-    accepted)."""
+    accepted).  ``sigma`` (per spatial orbital, +1 / -1) selects the NY
+    3-RDM of Eq. (8) for every map (not with the quadratic control, whose
+    slope is the Valdemoro adjoint)."""
+    sso = None if sigma is None else rdm.sigma_spin_orbital(sigma)
+    if sso is not None and control == QUADRATIC:
+        raise ValueError("the quadratic control's slope is built for the Valdemoro 3-RDM")
     h = np.asarray(h, dtype=np.float64)
     V = np.asarray(V, dtype=np.float64)
     r = h.shape[0]
@@ -109,7 +114,7 @@ def euler(h, V, N, gamma, d2aa, d2ab, eps=1e-3, de_tol=1e-6, max_iter=100, contr
     d2ab = np.array(d2ab, dtype=np.float64)
     _, d2 = rdm.blocks_to_spin_orbital(gamma, d2aa, d2ab)
     E = float(np.sum(K * d2))
-    R, f, d1, d2 = _residual(K, gamma, d2aa, d2ab)
+    R, f, d1, d2 = _residual(K, gamma, d2aa, d2ab, sso)
     out = dict(energy0=E, norm2_0=f, trials=[], iterations=0, stop=STOP_MAX_ITER, eps_last=0.0)
     e = eps
 
@@ -121,13 +126,13 @@ def euler(h, V, N, gamma, d2aa, d2ab, eps=1e-3, de_tol=1e-6, max_iter=100, contr
 
     for n in range(max_iter):
         Rm = R if mask is None else R * mask
-        U = residual_map(Rm, d1, d2, hermitian=False).numpy()
+        U = residual_map(Rm, d1, d2, hermitian=False, sigma_so=sso).numpy()
         uaa, uab = rdm.spin_orbital_to_blocks(U)
         raa, rab = rdm.spin_orbital_to_blocks(R)
 
         def run(x):
             a, b, g1, Et = _trial(K, N, d2aa, d2ab, uaa, uab, x)
-            Rt, ft, _, _ = _residual(K, g1, a, b)
+            Rt, ft, _, _ = _residual(K, g1, a, b, sso)
             return dict(eps=x, d2aa=a, d2ab=b, gamma=g1, E=Et, f=ft, R=Rt)
 
         trials = []

@@ -35,8 +35,8 @@ EXPORTS = ("acse_create", "acse_destroy", "acse_set_stream", "acse_residual", "a
            "acse_residual_vjp", "acse_energy_vjp", "acse_residual_batched",
            "acse_autotune_batched", "acse_solve")
 NUM_TILE_CONFIGS = 3
-NUM_STAGES = 6
-STAGES = ("rdm_operands", "fold", "transforms", "gemm", "assembly", "step_tail")
+NUM_STAGES = 7
+STAGES = ("rdm_operands", "fold", "transforms", "gemm", "assembly", "step_tail", "ny_share")
 
 
 class Problem(ctypes.Structure):
@@ -51,7 +51,10 @@ class ProfileData(ctypes.Structure):
 
 class Options(ctypes.Structure):
     _fields_ = [("precision", ctypes.c_int32), ("active", ctypes.c_void_p), ("tile", ctypes.c_int32),
-                ("flags", ctypes.c_int32)]
+                ("flags", ctypes.c_int32), ("reconstruction", ctypes.c_int32), ("ny_sigma", ctypes.c_void_p)]
+
+
+RECON_V, RECON_NY = 0, 1
 
 
 FLAG_GENERAL_KERNELS = 1
@@ -197,15 +200,24 @@ class Context:
         return prob, t
 
     @staticmethod
-    def options(precision="fp64", active=None, tile=-1, flags=0):
+    def options(precision="fp64", active=None, tile=-1, flags=0, sigma=None):
+        """acse_options.  ``sigma`` selects the Nakatsuji-Yasuda reconstruction:
+        True for the default reference occupations (orbitals below n_alpha
+        occupied) or a per-orbital sequence of +1 / -1; None is Valdemoro."""
         prec = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
         keep = None
         act = None
         if active is not None:
             keep = (ctypes.c_uint8 * len(active))(*[1 if a else 0 for a in active])
             act = ctypes.cast(keep, ctypes.c_void_p)
-        o = Options(prec, act, int(tile), int(flags))
-        o._keep = keep
+        recon, sig, keep_sig = RECON_V, None, None
+        if sigma is not None and sigma is not False:
+            recon = RECON_NY
+            if sigma is not True:
+                keep_sig = (ctypes.c_int8 * len(sigma))(*[int(x) for x in sigma])
+                sig = ctypes.cast(keep_sig, ctypes.c_void_p)
+        o = Options(prec, act, int(tile), int(flags), recon, sig)
+        o._keep = (keep, keep_sig)
         return o
 
     def residual_raw(self, prob, opts, R_aa, R_ab, want_norm=True):
@@ -214,23 +226,24 @@ class Context:
                                        _ptr(R_ab), ctypes.byref(n2) if want_norm else None))
         return n2.value
 
-    def residual(self, h, V, d1, d2aa, d2ab, n_alpha, precision="fp64", tile=-1, flags=0):
+    def residual(self, h, V, d1, d2aa, d2ab, n_alpha, precision="fp64", tile=-1, flags=0, sigma=None):
         """R_aa, R_ab (device, float64) and ||R||^2 of Eq. (4)."""
         prob, keep = self.problem(h, V, d1, d2aa, d2ab, n_alpha)
         r = prob.r
         R_aa = torch.empty((r, r, r, r), dtype=torch.float64, device=self.device)
         R_ab = torch.empty_like(R_aa)
-        n2 = self.residual_raw(prob, self.options(precision, None, tile, flags), R_aa, R_ab)
+        n2 = self.residual_raw(prob, self.options(precision, None, tile, flags, sigma), R_aa, R_ab)
         return R_aa, R_ab, n2
 
-    def update_map(self, h, V, d1, d2aa, d2ab, n_alpha, X_aa, X_ab, precision="fp64", tile=-1, flags=0):
+    def update_map(self, h, V, d1, d2aa, d2ab, n_alpha, X_aa, X_ab, precision="fp64", tile=-1, flags=0,
+                   sigma=None):
         """U = 1/2 <[a+a+aa, sum X a+a+aa]> for anti-Hermitian X (Eq. (9))."""
         prob, keep = self.problem(h, V, d1, d2aa, d2ab, n_alpha)
         X_aa, X_ab = _dev(X_aa, self.device), _dev(X_ab, self.device)
         U_aa = torch.empty_like(X_aa)
         U_ab = torch.empty_like(X_ab)
         self._check(_lib.acse_update_map(self._h, ctypes.byref(prob),
-                                         ctypes.byref(self.options(precision, None, tile, flags)),
+                                         ctypes.byref(self.options(precision, None, tile, flags, sigma)),
                                          _ptr(X_aa), _ptr(X_ab), _ptr(U_aa), _ptr(U_ab)))
         return U_aa, U_ab
 
@@ -255,7 +268,7 @@ class Context:
         return e.value, n2.value
 
     def step(self, h, V, d1, d2aa, d2ab, n_alpha, eps=1e-3, precision="fp64", active=None,
-             tile=-1, return_ru=False, flags=0):
+             tile=-1, return_ru=False, flags=0, sigma=None):
         """One Euler step of Eq. (9) on device copies; returns a dict with the new
         d1, d2aa, d2ab, the energy after the step and ||R||^2 before it."""
         prob, t = self.problem(h, V, d1, d2aa, d2ab, n_alpha)
@@ -264,7 +277,7 @@ class Context:
         bufs = [None] * 4
         if return_ru:
             bufs = [torch.empty((r, r, r, r), dtype=torch.float64, device=self.device) for _ in range(4)]
-        E, n2 = self.step_raw(prob, eps, self.options(precision, active, tile, flags), *bufs)
+        E, n2 = self.step_raw(prob, eps, self.options(precision, active, tile, flags, sigma), *bufs)
         if return_ru:
             extra = dict(R_aa=bufs[0], R_ab=bufs[1], U_aa=bufs[2], U_ab=bufs[3])
         return dict(d1=t[2], d2aa=t[3], d2ab=t[4], energy=E, norm2=n2, **extra)
@@ -279,7 +292,7 @@ class Context:
 
     def solve(self, h, V, d1, d2aa, d2ab, n_alpha, eps=1e-3, de_tol=1e-6, max_iter=100,
               control="fixed", max_halvings=8, eps_max=0.0, precision="fp64", active=None, tile=-1,
-              flags=0, capacity=256):
+              flags=0, capacity=256, sigma=None):
         """The Euler iteration of Eq. (9) with the stopping rules of the method
         section on device copies of the inputs (acse_solve).  Returns a dict with
         the final d1, d2aa, d2ab (device), energy/norm2 of the input and returned
@@ -289,7 +302,7 @@ class Context:
         so = SolveOptions(float(eps), float(de_tol), float(eps_max), int(max_iter),
                           CONTROLS[control] if isinstance(control, str) else int(control),
                           int(max_halvings), 0)
-        res, hist = self.solve_raw(prob, self.options(precision, active, tile, flags), so, capacity)
+        res, hist = self.solve_raw(prob, self.options(precision, active, tile, flags, sigma), so, capacity)
         return dict(d1=t[2], d2aa=t[3], d2ab=t[4], energy0=res.energy0, norm2_0=res.norm2_0,
                     energy=res.energy, norm2=res.norm2, eps=res.eps, iterations=res.iterations,
                     trial_count=res.trials, maps=res.maps, stop=STOP_REASONS[res.stop],

@@ -5,7 +5,7 @@ import subprocess
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libacse.so")
-SOURCES = ["acse_api.hip", "gemm.hip", "tensor_ops.hip", "vjp.hip"]
+SOURCES = ["acse_api.hip", "gemm.hip", "ny.hip", "tensor_ops.hip", "vjp.hip"]
 HIPCC_FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
     # no packed FP32 instructions in generated code

@@ -29,6 +29,8 @@
 #include <vector>
 
 #include "../../include/acse.h"
+#include "ny.h"
+#include "ny_plan.h"
 #include "tensor_ops.h"
 #include "vjp.h"
 
@@ -93,6 +95,16 @@ struct acse_ctx_s {
   // Euler driver workspace (allocated by the first acse_solve call)
   void *sbase = nullptr;
   int64_t sbytes = 0;
+  // Nakatsuji-Yasuda share (set by validate from the options of the call in
+  // progress; workspace allocated by the first call that uses it, for r_max)
+  bool ny_on = false;
+  std::vector<double> ny_sigma;     // per spatial orbital, +1 / -1
+  std::vector<double> ny_sigma_dev_copy;
+  acse::ny::Plan ny_plan;
+  bool ny_planned = false;
+  void *nybase = nullptr;
+  int64_t nybytes = 0;
+  int ny_r = 0;                     // r the operand buffers were last cleared for
 };
 
 namespace {
@@ -230,8 +242,24 @@ acse_status validate(acse_ctx c, const acse_problem *p, const acse_options *o, b
       return fail(c, ACSE_ERR_ARG, "tile configuration out of range");
     if (o->flags & ~(ACSE_FLAG_GENERAL_KERNELS | ACSE_FLAG_CHECK_INPUTS))
       return fail(c, ACSE_ERR_ARG, "unknown option flags");
+    if (o->reconstruction != ACSE_RECON_V && o->reconstruction != ACSE_RECON_NY)
+      return fail(c, ACSE_ERR_ARG, "unknown reconstruction");
+    if (o->reconstruction == ACSE_RECON_NY) {
+      if (o->precision != ACSE_FP64)
+        return fail(c, ACSE_ERR_UNSUPPORTED, "the Nakatsuji-Yasuda reconstruction is built for FP64 only");
+      if (o->ny_sigma)
+        for (int q = 0; q < p->r; ++q)
+          if (o->ny_sigma[q] != 1 && o->ny_sigma[q] != -1)
+            return fail(c, ACSE_ERR_ARG, "ny_sigma entries must be +1 or -1");
+    }
   }
   c->general = o && (o->flags & ACSE_FLAG_GENERAL_KERNELS);
+  c->ny_on = o && o->reconstruction == ACSE_RECON_NY;
+  if (c->ny_on) {
+    c->ny_sigma.assign(p->r, -1.0);
+    for (int q = 0; q < p->r; ++q)
+      c->ny_sigma[q] = o->ny_sigma ? (double)o->ny_sigma[q] : (q < p->n_alpha ? 1.0 : -1.0);
+  }
   if (o && (o->flags & ACSE_FLAG_CHECK_INPUTS)) return check_inputs(c, p, need_d1);
   return ACSE_OK;
 }
@@ -386,16 +414,172 @@ void map_probs(const Workspace &w, GemmPrec prec, int r, GemmProb *out) {
   set(5, OP_L3, OP_R3, -2.0, w.E3, (int)r2, (int)r2, ld, r, r2, r3, 1);   // rows (k,j), cols (i,l) -> [i,j,k,l]
 }
 
-// Stage 4 of F(X): assembly, (ij) <-> (kl) exchange, mask and the FP64 norm
-// 2||O_aa||^2 + 4||O_ab||^2 into norm_out (device).
-acse_status map_back(acse_ctx c, const acse_problem *p, double sigma, double *Oaa, double *Oab,
-                     const ActiveBits &act, double *Maa, double *Mab, double *norm_out,
-                     Workspace &w) {
+int map_cfg(acse_ctx c, GemmPrec prec, int r, int cfg) {
+  if (cfg >= 0) return cfg;
+  auto it = c->tuned.find({r, (int)prec});
+  const int r2 = r * r;
+  return it != c->tuned.end() ? it->second : gemm_default_cfg(prec, r2, r2);
+}
+
+// Nakatsuji-Yasuda workspace, sized for r_max: the seven source blocks and
+// the nine product blocks (natural r^4), the operand buffers of the plan, Y
+// and sigma.  Operand buffers are cleared whenever r changes (their padding
+// rows and columns must read as zero; the GEMMs and permutations write only
+// the r^2 x r^2 part of the intermediates).
+constexpr int kNySrc = 7, kNyProd = 9;
+struct NyPtrs {
+  double *src[kNySrc], *prod[kNyProd], *Y, *sig;
+  std::vector<double *> buf;
+};
+
+NyPtrs ny_carve(acse_ctx c, int r) {
+  NyPtrs q{};
+  const int64_t rm = c->r_max;
+  const int64_t nat = round_up(rm * rm * rm * rm * 8, 256);
+  const int64_t opb = round_up(op_rows(r) * op_ld(r) * 8, 256);
+  char *p = static_cast<char *>(c->nybase);
+  for (int k = 0; k < kNySrc; ++k) { q.src[k] = reinterpret_cast<double *>(p); p += nat; }
+  for (int k = 0; k < kNyProd; ++k) { q.prod[k] = reinterpret_cast<double *>(p); p += nat; }
+  q.Y = reinterpret_cast<double *>(p); p += round_up(rm * rm * 8, 256);
+  q.sig = reinterpret_cast<double *>(p); p += round_up(rm * 8, 256);
+  q.buf.resize(c->ny_plan.num_bufs);
+  for (int k = 0; k < c->ny_plan.num_bufs; ++k) { q.buf[k] = reinterpret_cast<double *>(p); p += opb; }
+  return q;
+}
+
+acse_status ensure_ny_ws(acse_ctx c) {
+  if (!c->ny_planned) {
+    c->ny_plan = ny::build_plan();
+    c->ny_planned = true;
+  }
+  if (c->nybase) return ACSE_OK;
+  const int64_t rm = c->r_max;
+  const int64_t nat = round_up(rm * rm * rm * rm * 8, 256);
+  const int64_t bytes = (kNySrc + kNyProd) * nat + round_up(rm * rm * 8, 256) + round_up(rm * 8, 256) +
+                        (int64_t)c->ny_plan.num_bufs * c->op_bytes;
+  if (hipMalloc(&c->nybase, bytes) != hipSuccess) {
+    (void)hipGetLastError();
+    c->nybase = nullptr;
+    return fail(c, ACSE_ERR_NOMEM, "Nakatsuji-Yasuda workspace allocation failed");
+  }
+  c->nybytes = bytes;
+  c->ny_r = 0;
+  return ACSE_OK;
+}
+
+// The NY share of F(X): S_aa -= C_aa, S_ab -= C_ab (C = B - B(k<->l), B the
+// 3-cumulant's share of the 3-RDM contraction), on the plan of ny_plan.h.
+acse_status ny_share(acse_ctx c, const acse_problem *p, const double *Xaa, const double *Xab,
+                     double *Saa, double *Sab) {
   const int r = p->r;
   hipStream_t s = c->stream;
-  StageTimer t4(c, 4);
-  HIP_TRY(c, launch_assemble(r, c->general, p->d1, w.t, w.Zaa, w.Zab,
-                             w.Zab + (int64_t)npair_le(r) * r * r, w.Pp, w.Pm, w.E3, w.Saa, w.Sab, s));
+  StageTimer t6(c, 6);
+  acse_status st = ensure_ny_ws(c);
+  if (st != ACSE_OK) return st;
+  const ny::Plan &P = c->ny_plan;
+  NyPtrs q = ny_carve(c, r);
+  const int64_t ld = op_ld(r), rows = op_rows(r), r2 = (int64_t)r * r;
+  bool upload = c->ny_sigma_dev_copy != c->ny_sigma;
+  if (c->ny_r != r) {
+    const int64_t opb = round_up(rows * ld * 8, 256);
+    HIP_TRY(c, launch_fill((int64_t)P.num_bufs * opb / 8, 0.0, q.buf[0], s));
+    c->ny_r = r;
+    upload = true;
+  }
+  if (upload) {
+    // the host vector lives in the context until the next change, after a synchronisation
+    HIP_TRY(c, hipStreamSynchronize(s));
+    c->ny_sigma_dev_copy = c->ny_sigma;
+    HIP_TRY(c, hipMemcpyAsync(q.sig, c->ny_sigma_dev_copy.data(), r * sizeof(double), hipMemcpyHostToDevice, s));
+  }
+  // sources: X blocks 0000 / 0101 / 0110, then D and sigma D
+  HIP_TRY(c, launch_ny_sources(r, p->d1, p->d2aa, p->d2ab, Xab, q.sig, q.src, s));
+  const double *src[3][3] = {{Xaa, Xab, q.src[6]}, {q.src[0], q.src[1], q.src[2]}, {q.src[3], q.src[4], q.src[5]}};
+  auto slot = [](int block) { return block == 0 ? 0 : block == 5 ? 1 : 2; };
+  const int64_t nst[4] = {r2 * r, r2, r, 1};
+  for (const ny::PermOp &op : P.perms) {
+    PermArgs a{};
+    a.r = r;
+    a.rows = rows;
+    a.ld = ld;
+    a.src1 = src[op.src][slot(op.block)];
+    for (int t = 0; t < 4; ++t) a.s1[t] = nst[P.layout_strides[4 * op.layout + t]];
+    a.c1 = 1.0;
+    a.src2 = nullptr;
+    a.c2 = 0.0;
+    a.accumulate = 0;
+    HIP_TRY(c, launch_permute4(GEMM_F64, a, OperandRef{q.buf[op.buf], nullptr}, s));
+  }
+  // GEMMs: stage by stage; within a stage, the t-th terms of all its output
+  // blocks go out together (distinct outputs), up to kMaxGemmProbs a launch
+  int ns = 0;
+  const ny::Stage *stg = ny::stages(&ns);
+  const int cfg = map_cfg(c, GEMM_F64, r, -1);
+  const int kp = gemm_kp(GEMM_F64, (int)r2, (int)ld);
+  for (int sidx = 0; sidx < ns; ++sidx) {
+    int64_t os[4];
+    ny::gemm_out_strides(stg[sidx], r, ld, os);
+    for (int term = 0;; ++term) {
+      std::vector<const ny::GemmOp *> round;
+      for (const ny::GemmOp &g : P.gemms)
+        if (g.stage == sidx && g.term == term) round.push_back(&g);
+      if (round.empty()) break;
+      for (size_t b0 = 0; b0 < round.size(); b0 += kMaxGemmProbs) {
+        GemmBatch batch{};
+        batch.count = (int)std::min<size_t>(kMaxGemmProbs, round.size() - b0);
+        for (int k = 0; k < batch.count; ++k) {
+          const ny::GemmOp &g = *round[b0 + k];
+          GemmProb &G = batch.p[k];
+          G = GemmProb{};
+          G.A = q.buf[g.a_buf];
+          G.B = q.buf[g.b_buf];
+          G.C = ny::is_product(g.out) ? q.prod[P.product_nat.at({g.out, g.block})]
+                                      : q.buf[P.inter_buf.at({g.out, g.block})];
+          G.alpha = 1.0;
+          G.M = (int)r2; G.N = (int)r2; G.Kp = kp; G.ld = (int)ld; G.rdiv = r;
+          G.sm1 = os[0]; G.sm0 = os[1]; G.sn1 = os[2]; G.sn0 = os[3];
+          G.ksplit = 1; G.kchunk = kp; G.accumulate = g.accumulate;
+        }
+        HIP_TRY(c, gemm_launch(GEMM_F64, cfg, batch, s));
+      }
+    }
+  }
+  HIP_TRY(c, launch_ny_trace_y(r, ld, q.buf[P.inter_buf.at({ny::T_W, 0})], q.buf[P.inter_buf.at({ny::T_W, 5})],
+                               q.Y, s));
+  NyCombineArgs a{};
+  const int pblk[3] = {0, 5, 6};
+  for (int b = 0; b < 3; ++b) {
+    a.il[b] = q.prod[P.product_nat.at({ny::T_IL, pblk[b]})];
+    a.ir[b] = q.prod[P.product_nat.at({ny::T_IR, pblk[b]})];
+    a.pr[b] = q.prod[P.product_nat.at({ny::T_PR, pblk[b]})];
+    a.sd[b] = q.src[3 + b];
+  }
+  a.Y = q.Y;
+  a.Saa = Saa;
+  a.Sab = Sab;
+  HIP_TRY(c, launch_ny_combine(r, a, s));
+  return ACSE_OK;
+}
+
+// Stage 4 of F(X): assembly, (ij) <-> (kl) exchange, mask and the FP64 norm
+// 2||O_aa||^2 + 4||O_ab||^2 into norm_out (device).  With the NY
+// reconstruction its share joins the assembled sum before the exchange.
+acse_status map_back(acse_ctx c, const acse_problem *p, double sigma, double *Oaa, double *Oab,
+                     const ActiveBits &act, double *Maa, double *Mab, double *norm_out,
+                     Workspace &w, const double *Xaa = nullptr, const double *Xab = nullptr) {
+  const int r = p->r;
+  hipStream_t s = c->stream;
+  {
+    StageTimer t4(c, 4);
+    HIP_TRY(c, launch_assemble(r, c->general, p->d1, w.t, w.Zaa, w.Zab,
+                               w.Zab + (int64_t)npair_le(r) * r * r, w.Pp, w.Pm, w.E3, w.Saa, w.Sab, s));
+  }
+  if (c->ny_on) {
+    if (!Xaa || !Xab) return fail(c, ACSE_ERR_UNSUPPORTED, "the NY share needs the map's X");
+    acse_status st = ny_share(c, p, Xaa, Xab, w.Saa, w.Sab);
+    if (st != ACSE_OK) return st;
+  }
+  StageTimer t4b(c, 4);
   HIP_TRY(c, launch_finish(r, sigma, w.Saa, w.Sab, w.Caa, w.Cab, Oaa, Oab, act, Maa, Mab,
                            w.partial, norm_out, s));
   return ACSE_OK;
@@ -424,7 +608,7 @@ acse_status run_map(acse_ctx c, const acse_problem *p, GemmPrec prec, int cfg, c
     StageTimer t3(c, 3);
     HIP_TRY(c, gemm_launch(prec, use_cfg, batch, c->stream));
   }
-  return map_back(c, p, sigma, Oaa, Oab, act, Maa, Mab, w.scal + slot, w);
+  return map_back(c, p, sigma, Oaa, Oab, act, Maa, Mab, w.scal + slot, w, Xaa, Xab);
 }
 
 ActiveBits make_bits(const acse_options *o, int r, bool *any) {
@@ -549,6 +733,7 @@ acse_status acse_destroy(acse_ctx ctx) {
   for (auto e : ctx->pool) (void)hipEventDestroy(e);
   if (ctx->vbase) (void)hipFree(ctx->vbase);
   if (ctx->sbase) (void)hipFree(ctx->sbase);
+  if (ctx->nybase) (void)hipFree(ctx->nybase);
   if (ctx->bbase) (void)hipFree(ctx->bbase);
   if (ctx->hdesc) (void)hipHostFree(ctx->hdesc);
   if (ctx->hdesc_done) (void)hipEventDestroy(ctx->hdesc_done);
@@ -594,6 +779,7 @@ acse_status acse_autotune(acse_ctx ctx, const acse_problem *prob, const acse_opt
                           int32_t *best_tile, double *times_ms) {
   acse_status st = validate(ctx, prob, opts);
   if (st != ACSE_OK) return st;
+  ctx->ny_on = false;  // the tile choice concerns the Valdemoro products; the NY ones share it
   if (!best_tile) return fail(ctx, ACSE_ERR_ARG, "best_tile is NULL");
   HIP_TRY(ctx, hipSetDevice(ctx->device));
   const GemmPrec prec = prec_of(opts);
@@ -770,6 +956,7 @@ extern "C" acse_status acse_residual_vjp(acse_ctx ctx, const acse_problem *prob,
                                          double *d1_bar, double *d2aa_bar, double *d2ab_bar) {
   acse_status st = validate(ctx, prob, opts);
   if (st != ACSE_OK) return st;
+  if (ctx->ny_on) return fail(ctx, ACSE_ERR_UNSUPPORTED, "the adjoint is built for the Valdemoro reconstruction only");
   for (const void *q : {static_cast<const void *>(Rbar_aa), static_cast<const void *>(Rbar_ab),
                         static_cast<const void *>(h_bar), static_cast<const void *>(V_bar),
                         static_cast<const void *>(d1_bar), static_cast<const void *>(d2aa_bar),
@@ -1311,6 +1498,8 @@ extern "C" acse_status acse_solve(acse_ctx ctx, acse_problem *prob, const acse_o
   if ((st = check_solve_options(ctx, so, res, hist, cap)) != ACSE_OK) return st;
   HIP_TRY(ctx, hipSetDevice(ctx->device));
   const bool quad = so->control == ACSE_EULER_QUADRATIC;
+  if (quad && ctx->ny_on)
+    return fail(ctx, ACSE_ERR_UNSUPPORTED, "the quadratic control needs the adjoint, built for the Valdemoro reconstruction only");
   SolveWs sw{};
   if ((st = ensure_solve_ws(ctx, quad, sw)) != ACSE_OK) return st;
   if (quad && (st = ensure_vjp_ws(ctx)) != ACSE_OK) return st;
@@ -1502,6 +1691,7 @@ acse_status validate_batch(acse_ctx c, int32_t count, const acse_problem *probs,
     acse_status st = validate(c, &probs[i], opts);
     if (st != ACSE_OK) return fail(c, st, "instance " + std::to_string(i) + ": " + c->err);
   }
+  if (c->ny_on) return fail(c, ACSE_ERR_UNSUPPORTED, "the batched residual is built for the Valdemoro reconstruction only");
   return ACSE_OK;
 }
 

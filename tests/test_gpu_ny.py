@@ -1,0 +1,198 @@
+"""GPU parity of the Nakatsuji-Yasuda reconstruction (Eq. (8); App. D, NY
+part) against the oracle (tier B with the NY share, pinned in
+test_oracle_ny.py).
+
+* Residual at r = 4, 9, 16 (r^2 = 16 .. 256: one to two GEMM tiles with ragged
+  edges) with the default reference occupations and with sigma patterns that
+  are not a prefix; FP64 bar 1e-10 of the largest element, on the residual
+  and, separately, on the NY share alone (NY residual minus Valdemoro
+  residual, both from the same side), so a wrong share cannot hide below the
+  Valdemoro part.
+* One Euler step (both maps with the NY 3-RDM) and the Euler driver with the
+  fixed control, against the oracle's step and iteration.
+* r = 50 (the headline size): the identities that hold at any size, E1 - E0 =
+  -eps ||R||^2 and Tr U = 0 per block, and the share is nonzero.
+* r = 96 (the largest r): a closed-shell determinant has 2Delta = 0, so the
+  NY residual equals the closed form of the Valdemoro one.
+* Rejected combinations: FP32 / split BF16, the adjoint, the quadratic
+  control, the batched residual, sigma entries other than +1 / -1.
+"""
+import numpy as np
+import pytest
+
+import determinant_forms as dform
+from oracle import rdm
+from oracle import solve as sv
+from oracle import step as ost
+from synth import generators as gen
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def acse():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.fail("no GPU visible")
+    import paper_2604_02550_amd as acse
+    return acse
+
+
+def correlated(r, N, seed, scale=0.05):
+    """A generated problem with a larger 2-cumulant (the NY share is quadratic in it)."""
+    p = gen.problem(r, N, 8, seed=seed)
+    extra = gen.symmetric_direction(np.random.default_rng(seed + 100), r, scale=scale)
+    p["d2aa"] = p["d2aa"] + extra["d2aa"]
+    p["d2ab"] = p["d2ab"] + extra["d2ab"]
+    return p
+
+
+def sigma_of(p, pattern):
+    if pattern == "prefix":
+        return np.where(np.arange(p["r"]) < p["N"] // 2, 1.0, -1.0)
+    return np.array(pattern, dtype=float)
+
+
+CASES = [(4, 4, 0, "prefix"), (4, 4, 1, (-1, 1, -1, 1)), (9, 8, 2, "prefix"),
+         (9, 8, 3, (1, -1, 1, 1, -1, 1, -1, -1, 1)), (16, 10, 4, "prefix")]
+
+
+@pytest.mark.parametrize("r,N,seed,pattern", CASES)
+def test_ny_residual_matches_oracle(acse, r, N, seed, pattern):
+    p = correlated(r, N, seed)
+    sig = sigma_of(p, pattern)
+    print(f"[ny] residual r={r} N={N} seed={seed} sigma={pattern}", flush=True)
+    oaa, oab, on2 = ost.residual(p["h"], p["V"], N, p["gamma"], p["d2aa"], p["d2ab"], sigma=sig)
+    vaa, vab, _ = ost.residual(p["h"], p["V"], N, p["gamma"], p["d2aa"], p["d2ab"])
+    ctx = acse.Context(r_max=r)
+    try:
+        arg = True if pattern == "prefix" else [int(x) for x in sig]
+        Raa, Rab, n2 = ctx.residual(p["h"], p["V"], p["gamma"], p["d2aa"], p["d2ab"], N // 2, sigma=arg)
+        Vaa, Vab, _ = ctx.residual(p["h"], p["V"], p["gamma"], p["d2aa"], p["d2ab"], N // 2)
+        Raa, Rab, Vaa, Vab = (x.cpu().numpy() for x in (Raa, Rab, Vaa, Vab))
+    finally:
+        ctx.close()
+    scale = max(np.abs(oaa).max(), np.abs(oab).max())
+    assert np.abs(Raa - oaa).max() <= 1e-10 * scale
+    assert np.abs(Rab - oab).max() <= 1e-10 * scale
+    assert abs(n2 - on2) <= 1e-10 * on2
+    share = max(np.abs(oaa - vaa).max(), np.abs(oab - vab).max())
+    assert share > 1e-4 * scale
+    assert np.abs((Raa - Vaa) - (oaa - vaa)).max() <= 1e-9 * share
+    assert np.abs((Rab - Vab) - (oab - vab)).max() <= 1e-9 * share
+
+
+def test_ny_step_matches_oracle(acse):
+    r, N = 9, 8
+    p = correlated(r, N, 5)
+    sig = sigma_of(p, "prefix")
+    print(f"[ny] step r={r}", flush=True)
+    o = ost.step(p["h"], p["V"], N, p["gamma"], p["d2aa"], p["d2ab"], 1e-3, sigma=sig)
+    ctx = acse.Context(r_max=r)
+    try:
+        g = ctx.step(p["h"], p["V"], p["gamma"], p["d2aa"], p["d2ab"], N // 2, eps=1e-3, return_ru=True,
+                     sigma=True)
+        for key in ("R_aa", "R_ab", "U_aa", "U_ab", "d2aa", "d2ab"):
+            x = g[key].cpu().numpy()
+            assert np.abs(x - o[key]).max() <= 1e-10 * np.abs(o[key]).max(), key
+        assert np.abs(g["d1"].cpu().numpy() - o["gamma"]).max() <= 1e-10 * np.abs(o["gamma"]).max()
+        assert abs(g["energy"] - o["energy"]) <= 1e-12 * abs(o["energy"])
+        assert abs(g["norm2"] - o["norm2"]) <= 1e-10 * o["norm2"]
+    finally:
+        ctx.close()
+
+
+def test_ny_solve_matches_oracle(acse):
+    r, N = 6, 4
+    p = gen.problem(r, N, 12, seed=1)
+    _, d2 = rdm.blocks_to_spin_orbital(np.eye(r), p["d2aa"], p["d2ab"])
+    p["gamma"] = rdm.contract_to_1rdm(d2, N)[:r, :r]
+    sig = sigma_of(p, "prefix")
+    print(f"[ny] solve r={r}", flush=True)
+    o = sv.euler(p["h"], p["V"], N, p["gamma"], p["d2aa"], p["d2ab"], eps=1e-3, de_tol=1e-9, max_iter=3,
+                 control=sv.FIXED, sigma=sig)
+    ctx = acse.Context(r_max=r)
+    try:
+        g = ctx.solve(p["h"], p["V"], p["gamma"], p["d2aa"], p["d2ab"], N // 2, eps=1e-3, de_tol=1e-9,
+                      max_iter=3, control="fixed", sigma=True)
+    finally:
+        ctx.close()
+    assert g["iterations"] == o["iterations"] and len(g["trials"]) == len(o["trials"])
+    for (ge, gE, gf, gn, ga), (oe, oE, of, on, oa) in zip(g["trials"], o["trials"]):
+        assert gn == on and ga == oa and ge == oe
+        assert abs(gE - oE) <= 1e-10 * max(1.0, abs(oE))
+        assert abs(gf - of) <= 1e-10 * of
+    for key in ("d2aa", "d2ab"):
+        assert np.abs(g[key].cpu().numpy() - o[key]).max() <= 1e-10 * np.abs(o[key]).max(), key
+
+
+def test_ny_r50_identities(acse):
+    p = gen.named("r50")
+    r, N = p["r"], p["N"]
+    eps = 1e-3
+    print(f"[ny] r={r} identities", flush=True)
+    ctx = acse.Context(r_max=r)
+    try:
+        E0 = ctx.energy(p["h"], p["V"], p["d2aa"], p["d2ab"], N // 2)
+        Vaa, Vab, _ = ctx.residual(p["h"], p["V"], p["gamma"], p["d2aa"], p["d2ab"], N // 2)
+        out = ctx.step(p["h"], p["V"], p["gamma"], p["d2aa"], p["d2ab"], N // 2, eps=eps, return_ru=True,
+                       sigma=True)
+        n2 = out["norm2"]
+        assert abs((out["energy"] - E0) + eps * n2) <= 1e-9 * eps * n2
+        for Ub in (out["U_aa"], out["U_ab"]):
+            umax = float(Ub.abs().max())
+            tr = float(Ub.reshape(r * r, r * r).diagonal().sum())
+            assert abs(tr) <= 1e-12 * umax * r * r
+        share = max(float((out["R_aa"] - Vaa).abs().max()), float((out["R_ab"] - Vab).abs().max()))
+        assert share > 1e-8 * float(out["R_ab"].abs().max())
+    finally:
+        ctx.close()
+
+
+def test_ny_r96_determinant(acse):
+    r, na = 96, 29
+    print(f"[ny] r={r} closed-shell determinant", flush=True)
+    rng = np.random.default_rng(7)
+    h, V = gen.hamiltonian(rng, r, 96)
+    g, d2aa, d2ab = dform.rdms(r, na)
+    caa, cab = dform.residual_blocks(h, V, na)
+    U = gen.haar_orthogonal(rng, r)
+    rot = dform.rot4
+    inputs = (dform.rot2(h, U), rot(V, U), dform.rot2(g, U), rot(d2aa, U), rot(d2ab, U))
+    del V, d2aa, d2ab
+    exp_aa, exp_ab = rot(caa, U), rot(cab, U)
+    del caa, cab
+    ctx = acse.Context(r_max=r)
+    try:
+        Raa, Rab, _ = ctx.residual(*inputs, na, sigma=True)
+        scale = max(np.abs(exp_aa).max(), np.abs(exp_ab).max())
+        assert np.abs(Raa.cpu().numpy() - exp_aa).max() <= 1e-10 * scale
+        assert np.abs(Rab.cpu().numpy() - exp_ab).max() <= 1e-10 * scale
+    finally:
+        ctx.close()
+
+
+def test_ny_rejected_combinations(acse):
+    import torch
+    p = correlated(4, 4, 0)
+    ctx = acse.Context(r_max=4)
+    try:
+        for prec in ("fp32", "bf16x3"):
+            with pytest.raises(acse.AcseError, match="FP64 only"):
+                ctx.residual(p["h"], p["V"], p["gamma"], p["d2aa"], p["d2ab"], 2, precision=prec, sigma=True)
+        with pytest.raises(acse.AcseError, match="ny_sigma"):
+            ctx.residual(p["h"], p["V"], p["gamma"], p["d2aa"], p["d2ab"], 2, sigma=[1, 0, -1, -1])
+        with pytest.raises(acse.AcseError, match="quadratic"):
+            ctx.solve(p["h"], p["V"], p["gamma"], p["d2aa"], p["d2ab"], 2, control="quadratic", sigma=True)
+        prob, keep = ctx.problem(p["h"], p["V"], p["gamma"], p["d2aa"], p["d2ab"], 2)
+        z = [torch.zeros((4, 4, 4, 4), dtype=torch.float64, device="cuda") for _ in range(5)]
+        zs = [torch.zeros((4, 4), dtype=torch.float64, device="cuda") for _ in range(2)]
+        opts = ctx.options("fp64", sigma=True)
+        with pytest.raises(acse.AcseError, match="adjoint"):
+            ctx.residual_vjp_raw(prob, opts, z[0], z[1], zs[0], z[2], zs[1], z[3], z[4])
+        # the Valdemoro path is unaffected afterwards
+        Raa, Rab, n2 = ctx.residual(p["h"], p["V"], p["gamma"], p["d2aa"], p["d2ab"], 2)
+        o = ost.residual(p["h"], p["V"], 4, p["gamma"], p["d2aa"], p["d2ab"])
+        assert abs(n2 - o[2]) <= 1e-10 * o[2]
+    finally:
+        ctx.close()
