@@ -59,6 +59,8 @@ def parse():
     ap.add_argument("--solve-controls", default="fixed,backtrack,quadratic",
                     help="step controls of acse_solve timed on the workload (FP64); empty to skip")
     ap.add_argument("--solve-iters", type=int, default=5)
+    ap.add_argument("--ny-steps", type=int, default=5,
+                    help="steps of the Nakatsuji-Yasuda leg (FP64); 0 skips it")
     ap.add_argument("--solve-eps", type=float, default=1e-5,
                     help="first step size of the acse_solve leg (the synthetic r = 50 integrals are "
                          "large: eps = 1e-3 raises ||R|| at the first trial)")
@@ -209,6 +211,51 @@ def bench_solve(acse, ctx, prob, work, pristine, torch, controls, iters, eps, st
     for w, q in zip(work, pristine):
         w.copy_(q)
     return res
+
+
+NY_BLOCK_GEMMS = 28  # spatial-block products of the NY share per map (the plan of ny_plan.h)
+
+
+def bench_ny(acse, ctx, prob, work, pristine, torch, stream, steps, warmup, eps, v_step_ms):
+    """One acse_step with the Nakatsuji-Yasuda 3-RDM (Eq. (8)) on the same
+    workload, FP64: ms per step, the stage split with the NY share's own
+    stage, and the share's rate in issued block-GEMM flops (28 products of
+    2 r^6 per map) per second of its stage (permutations, cumulant blocks and
+    the combination included).  The check is E1 - E0 = -eps ||R||^2."""
+    r = prob.r
+    opts = acse.Context.options("fp64", sigma=True)
+
+    def restore():
+        for w, q in zip(work, pristine):
+            w.copy_(q)
+
+    for _ in range(warmup):
+        restore()
+        ctx.step_raw(prob, eps, opts, want=False)
+    torch.cuda.synchronize()
+    ctx.profile(True)
+    start = torch.cuda.Event(enable_timing=True)
+    stop = torch.cuda.Event(enable_timing=True)
+    start.record(stream)
+    for _ in range(steps):
+        restore()
+        ctx.step_raw(prob, eps, opts, want=False)
+    stop.record(stream)
+    torch.cuda.synchronize()
+    ms = start.elapsed_time(stop) / steps
+    prof = ctx.profile_read()
+    ctx.profile(False)
+    restore()
+    E0 = ctx.energy_raw(prob)
+    E1, n2 = ctx.step_raw(prob, eps, opts)
+    restore()
+    ny_ms = prof["ny_share"][0] / steps
+    flops = 2 * NY_BLOCK_GEMMS * 2.0 * r ** 6
+    return dict(ms_per_step=ms, steps_per_s=1e3 / ms, over_valdemoro_step=ms / v_step_ms,
+                stage_ms_per_step={k: v[0] / steps for k, v in prof.items()},
+                ny_share_ms_per_step=ny_ms, ny_block_gemm_flops_per_step=flops,
+                ny_share_tflops=flops / (ny_ms * 1e-3) / 1e12,
+                energy_identity_rel=abs((E1 - E0) + eps * n2) / (eps * n2))
 
 
 def src_hash():
@@ -364,6 +411,10 @@ def main():
     if args.solve_controls:
         line["solve"] = bench_solve(acse, ctx, prob, work, pristine, torch, args.solve_controls.split(","),
                                     args.solve_iters, args.solve_eps, results.get("fp64", hr)["ms_per_step"])
+    if args.ny_steps > 0:
+        line["nakatsuji_yasuda"] = bench_ny(acse, ctx, prob, work, pristine, torch, stream, args.ny_steps,
+                                            min(args.warmup, 2), args.eps,
+                                            results.get("fp64", hr)["ms_per_step"])
     if args.vjp_modes:
         line["vjp"] = bench_vjp(acse, gen, torch, args.vjp_modes.split(","), max(3, args.steps // 2),
                                 args.warmup)

@@ -113,7 +113,7 @@ typedef struct {
  *   ACSE_RECON_NY  Nakatsuji-Yasuda: the 3-cumulant is approximated by the
  *                  sigma-weighted, antisymmetrised product of two 2-cumulants
  *                  of Eq. (8) (App. D, NY part), never formed.  Both maps of
- *                  a step use it.  Its share runs as 30 spatial-block FP64
+ *                  a step use it.  Its share runs as 28 spatial-block FP64
  *                  GEMMs of r^2 x r^2 x r^2 per map (a spin-orbital contraction
  *                  split over the spins of its internal indices), so it is
  *                  FP64 only: another precision is ACSE_ERR_UNSUPPORTED, as are

@@ -426,7 +426,7 @@ int map_cfg(acse_ctx c, GemmPrec prec, int r, int cfg) {
 // and sigma.  Operand buffers are cleared whenever r changes (their padding
 // rows and columns must read as zero; the GEMMs and permutations write only
 // the r^2 x r^2 part of the intermediates).
-constexpr int kNySrc = 7, kNyProd = 9;
+constexpr int kNySrc = 7, kNyProd = 12;  // 9 products + the 3 blocks of B
 struct NyPtrs {
   double *src[kNySrc], *prod[kNyProd], *Y, *sig;
   std::vector<double *> buf;
@@ -510,32 +510,34 @@ acse_status ny_share(acse_ctx c, const acse_problem *p, const double *Xaa, const
     a.accumulate = 0;
     HIP_TRY(c, launch_permute4(GEMM_F64, a, OperandRef{q.buf[op.buf], nullptr}, s));
   }
-  // GEMMs: stage by stage; within a stage, the t-th terms of all its output
-  // blocks go out together (distinct outputs), up to kMaxGemmProbs a launch
+  // GEMMs in two phases (the first-stage products, then the second stages
+  // that read them); within a phase the t-th terms of all output blocks go out
+  // together (distinct outputs), up to kMaxGemmProbs a launch, so a launch
+  // holds several r^2 x r^2 products and fills the chip
   int ns = 0;
   const ny::Stage *stg = ny::stages(&ns);
   const int cfg = map_cfg(c, GEMM_F64, r, -1);
   const int kp = gemm_kp(GEMM_F64, (int)r2, (int)ld);
-  for (int sidx = 0; sidx < ns; ++sidx) {
-    int64_t os[4];
-    ny::gemm_out_strides(stg[sidx], r, ld, os);
+  for (int phase = 0; phase < 2; ++phase) {
     for (int term = 0;; ++term) {
       std::vector<const ny::GemmOp *> round;
       for (const ny::GemmOp &g : P.gemms)
-        if (g.stage == sidx && g.term == term) round.push_back(&g);
+        if ((g.stage >= ns / 2) == (phase == 1) && g.term == term) round.push_back(&g);
       if (round.empty()) break;
       for (size_t b0 = 0; b0 < round.size(); b0 += kMaxGemmProbs) {
         GemmBatch batch{};
         batch.count = (int)std::min<size_t>(kMaxGemmProbs, round.size() - b0);
         for (int k = 0; k < batch.count; ++k) {
           const ny::GemmOp &g = *round[b0 + k];
+          int64_t os[4];
+          ny::gemm_out_strides(stg[g.stage], r, ld, os);
           GemmProb &G = batch.p[k];
           G = GemmProb{};
           G.A = q.buf[g.a_buf];
           G.B = q.buf[g.b_buf];
           G.C = ny::is_product(g.out) ? q.prod[P.product_nat.at({g.out, g.block})]
                                       : q.buf[P.inter_buf.at({g.out, g.block})];
-          G.alpha = 1.0;
+          G.alpha = g.alpha;
           G.M = (int)r2; G.N = (int)r2; G.Kp = kp; G.ld = (int)ld; G.rdiv = r;
           G.sm1 = os[0]; G.sm0 = os[1]; G.sn1 = os[2]; G.sn0 = os[3];
           G.ksplit = 1; G.kchunk = kp; G.accumulate = g.accumulate;
@@ -555,6 +557,7 @@ acse_status ny_share(acse_ctx c, const acse_problem *p, const double *Xaa, const
     a.sd[b] = q.src[3 + b];
   }
   a.Y = q.Y;
+  for (int b = 0; b < 3; ++b) a.B[b] = q.prod[kNyProd - 3 + b];
   a.Saa = Saa;
   a.Sab = Sab;
   HIP_TRY(c, launch_ny_combine(r, a, s));

@@ -53,31 +53,45 @@ k_ny_trace_y(int r, int64_t ld, const double *__restrict__ W0, const double *__r
   Y[e] = acc;
 }
 
-__global__ void __launch_bounds__(256) k_ny_combine(int r, NyCombineArgs a) {
+__global__ void __launch_bounds__(256) k_ny_bsum(int r, NyCombineArgs a) {
   const int64_t r2 = (int64_t)r * r;
   const int64_t e = tid64();
   if (e >= r2 * r2) return;
-  const int l = (int)(e % r);
-  int64_t t = e / r;
-  const int k = (int)(t % r);
-  t /= r;
-  const int j = (int)(t % r);
-  const int i = (int)(t / r);
-  auto at = [&](const double *T, int x0, int x1, int x2, int x3) {
-    return T[((int64_t)(x0 * r + x1) * r + x2) * r + x3];
-  };
-  auto bv = [&](int b, int x0, int x1, int x2, int x3) {
+  const int64_t kl = e % r2;
+  const int64_t ij = e / r2;
+  const int j = (int)(ij % r), i = (int)(ij / r);
+  const int k = (int)(kl / r), l = (int)(kl % r);
+  const int64_t ji = ((int64_t)j * r + i) * r2 + kl;  // the i <-> j exchanged element
+  const double *y = a.Y + (int64_t)k * r;
+#pragma unroll
+  for (int b = 0; b < 3; ++b) {
     const int bs = b == 0 ? 0 : 3 - b;  // block with the spins of i and j exchanged
+    const double *sd = a.sd[b] + ij * r2 + l;
     double pl = 0.0;
-    const double *sd = a.sd[b] + (int64_t)(x0 * r + x1) * r2 + x3;
-    const double *y = a.Y + (int64_t)x2 * r;
     for (int q = 0; q < r; ++q) pl += y[q] * sd[(int64_t)q * r];
-    return 4.0 * (at(a.il[b], x0, x1, x2, x3) - at(a.il[bs], x1, x0, x2, x3) + pl -
-                  2.0 * at(a.ir[b], x0, x1, x2, x3) + 2.0 * at(a.ir[bs], x1, x0, x2, x3) -
-                  2.0 * at(a.pr[b], x0, x1, x2, x3));
-  };
-  a.Saa[e] -= bv(0, i, j, k, l) - bv(0, i, j, l, k);
-  a.Sab[e] -= bv(1, i, j, k, l) - bv(2, i, j, l, k);
+    a.B[b][e] = 4.0 * (a.il[b][e] - a.il[bs][ji] + pl - 2.0 * a.ir[b][e] + 2.0 * a.ir[bs][ji] - 2.0 * a.pr[b][e]);
+  }
+}
+
+// One block per (i,j) slab: S_aa -= B0 - B0^T, S_ab -= B1 - B2^T, T the
+// exchange of k and l within the slab, read from LDS.
+__global__ void __launch_bounds__(256) k_ny_sub(int r, NyCombineArgs a) {
+  extern __shared__ double lds[];
+  const int rp = r + 1;
+  double *t0 = lds, *t2 = lds + (int64_t)r * rp;
+  const int64_t r2 = (int64_t)r * r;
+  const int64_t base = (int64_t)blockIdx.x * r2;
+  for (int64_t x = threadIdx.x; x < r2; x += 256) {
+    const int k = (int)(x / r), l = (int)(x % r);
+    t0[k * rp + l] = a.B[0][base + x];
+    t2[k * rp + l] = a.B[2][base + x];
+  }
+  __syncthreads();
+  for (int64_t x = threadIdx.x; x < r2; x += 256) {
+    const int k = (int)(x / r), l = (int)(x % r);
+    a.Saa[base + x] -= t0[k * rp + l] - t0[l * rp + k];
+    a.Sab[base + x] -= a.B[1][base + x] - t2[l * rp + k];
+  }
 }
 
 }  // namespace
@@ -96,8 +110,13 @@ hipError_t launch_ny_trace_y(int r, int64_t ld, const double *W0, const double *
 }
 
 hipError_t launch_ny_combine(int r, const NyCombineArgs &a, hipStream_t s) {
-  const int64_t n = (int64_t)r * r * r * r;
-  hipLaunchKernelGGL(k_ny_combine, grid_for(n), dim3(256), 0, s, r, a);
+  const int64_t r2 = (int64_t)r * r;
+  hipLaunchKernelGGL(k_ny_bsum, grid_for(r2 * r2), dim3(256), 0, s, r, a);
+  const size_t lds = (size_t)2 * r * (r + 1) * sizeof(double);
+  hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(&k_ny_sub),
+                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_ny_sub, dim3((unsigned)r2), dim3(256), lds, s, r, a);
   return hipGetLastError();
 }
 

@@ -108,7 +108,15 @@ struct GemmOp {
   int stage;
   int accumulate;     // 0 for the first term of an output block
   int term;           // term index within the output block
+  double alpha;       // 2 where the term stands for itself and its pair-exchanged twin
 };
+
+// K letters that are the two indices of one pair (positions 0,1 or 2,3) of a
+// source tensor: the source is antisymmetric under their exchange.
+inline bool source_pair(const char *nat, const char *k) {
+  const int a = letter_pos(nat, k[0]), b = letter_pos(nat, k[1]);
+  return a >= 0 && b >= 0 && (a >> 1) == (b >> 1);
+}
 
 struct Plan {
   std::vector<std::string> layouts;      // source letters + row/K letters, per PermOp
@@ -133,8 +141,11 @@ inline Plan build_plan() {
     return produced.count({t, canon(b)}) > 0;
   };
   std::vector<std::map<int, std::vector<std::pair<int, int>>>> terms(ns);
+  std::vector<std::map<int, std::vector<double>>> alphas(ns);
+  std::vector<bool> twin_pairs(ns);
   for (int s = 0; s < ns; ++s) {
     const Stage &S = st[s];
+    twin_pairs[s] = is_source(S.a) && is_source(S.b) && source_pair(S.la, S.ka) && source_pair(S.lb, S.kb);
     std::string letters;
     for (const char *q : {S.la, S.lb})
       for (int t = 0; t < 4; ++t)
@@ -146,7 +157,16 @@ inline Plan build_plan() {
       const int ba = block_of(S.la, spin), bb = block_of(S.lb, spin), bo = block_of(S.lo, spin);
       if (bo & 8) continue;  // canonical outputs only
       if (!nonzero(S.a, ba) || !nonzero(S.b, bb)) continue;
+      // Where the summed index pair is one antisymmetric pair of both
+      // (source) operands, the terms with its two spins exchanged are equal:
+      // keep the one with the first K index alpha, counted twice.
+      double alpha = 1.0;
+      if (twin_pairs[s] && spin.at(S.ka[0]) != spin.at(S.ka[1])) {
+        if (spin.at(S.ka[0]) == 1) continue;
+        alpha = 2.0;
+      }
       terms[s][bo].push_back({ba, bb});
+      alphas[s][bo].push_back(alpha);
     }
     for (auto &kv : terms[s]) produced.insert({S.out, kv.first});
   }
@@ -205,8 +225,10 @@ inline Plan build_plan() {
         P.inter_buf[{S.out, bo}] = P.num_bufs++;
       }
       int term = 0;
+      const std::vector<double> &al = alphas[s][bo];
       for (auto &ab : kv.second) {
         GemmOp g{};
+        g.alpha = al[term];
         g.a_buf = operand(S.a, ab.first, S.la, S.ra, S.ka);
         g.b_buf = operand(S.b, ab.second, S.lb, S.rb, S.kb);
         g.out = S.out;
