@@ -18,9 +18,10 @@ hipError_t launch_ny_trace_y(int r, int64_t ld, const double *W0, const double *
 // S_aa -= C_aa, S_ab -= C_ab with C = B - B(k<->l) and
 // B = 4 [sw(T_il) + T_pl - 2 sw(T_ir) - 2 T_pr] on the canonical blocks
 // 0000, 0101, 0110 (slots 0, 1, 2); T_pl = sum_a Y[k,a] SD[i,j,a,l].
-// Two passes: the B blocks (natural, coalesced: the i <-> j exchange swaps
-// whole (k,l) slabs) into B[0..2], then the k <-> l exchange through a slab in
-// LDS.  Needs 2 r (r+1) doubles of LDS (r <= 96: 149 KB).
+// Two passes, one block per (i,j) slab each: the B blocks into B[0..2] (the
+// i <-> j exchange reads whole (k,l) slabs; Y and the SD slab in LDS), then
+// the k <-> l exchange through slabs in LDS.  Each needs 2 r (r+1) doubles of
+// LDS (r <= 96: 149 KB).
 struct NyCombineArgs {
   const double *il[3], *ir[3], *pr[3], *sd[3];
   const double *Y;

@@ -53,23 +53,31 @@ k_ny_trace_y(int r, int64_t ld, const double *__restrict__ W0, const double *__r
   Y[e] = acc;
 }
 
+// One block per (i,j) slab: Y and the slab SD(b)[i,j,:,:] in LDS, so the
+// r-term sums of T_pl read LDS; the other terms are read along (k,l).
 __global__ void __launch_bounds__(256) k_ny_bsum(int r, NyCombineArgs a) {
+  extern __shared__ double lds[];
+  const int rp = r + 1;
+  double *ys = lds, *ss = lds + (int64_t)r * rp;
   const int64_t r2 = (int64_t)r * r;
-  const int64_t e = tid64();
-  if (e >= r2 * r2) return;
-  const int64_t kl = e % r2;
-  const int64_t ij = e / r2;
-  const int j = (int)(ij % r), i = (int)(ij / r);
-  const int k = (int)(kl / r), l = (int)(kl % r);
-  const int64_t ji = ((int64_t)j * r + i) * r2 + kl;  // the i <-> j exchanged element
-  const double *y = a.Y + (int64_t)k * r;
-#pragma unroll
+  const int64_t ij = blockIdx.x;
+  const int i = (int)(ij / r), j = (int)(ij % r);
+  const int64_t base = ij * r2, jib = ((int64_t)j * r + i) * r2;
+  for (int64_t x = threadIdx.x; x < r2; x += 256) ys[(x / r) * rp + x % r] = a.Y[x];
+#pragma unroll 1
   for (int b = 0; b < 3; ++b) {
     const int bs = b == 0 ? 0 : 3 - b;  // block with the spins of i and j exchanged
-    const double *sd = a.sd[b] + ij * r2 + l;
-    double pl = 0.0;
-    for (int q = 0; q < r; ++q) pl += y[q] * sd[(int64_t)q * r];
-    a.B[b][e] = 4.0 * (a.il[b][e] - a.il[bs][ji] + pl - 2.0 * a.ir[b][e] + 2.0 * a.ir[bs][ji] - 2.0 * a.pr[b][e]);
+    __syncthreads();
+    for (int64_t x = threadIdx.x; x < r2; x += 256) ss[(x / r) * rp + x % r] = a.sd[b][base + x];
+    __syncthreads();
+    for (int64_t x = threadIdx.x; x < r2; x += 256) {
+      const int k = (int)(x / r), l = (int)(x % r);
+      const double *y = ys + k * rp;
+      double pl = 0.0;
+      for (int q = 0; q < r; ++q) pl += y[q] * ss[q * rp + l];
+      a.B[b][base + x] = 4.0 * (a.il[b][base + x] - a.il[bs][jib + x] + pl - 2.0 * a.ir[b][base + x] +
+                                2.0 * a.ir[bs][jib + x] - 2.0 * a.pr[b][base + x]);
+    }
   }
 }
 
@@ -111,11 +119,12 @@ hipError_t launch_ny_trace_y(int r, int64_t ld, const double *W0, const double *
 
 hipError_t launch_ny_combine(int r, const NyCombineArgs &a, hipStream_t s) {
   const int64_t r2 = (int64_t)r * r;
-  hipLaunchKernelGGL(k_ny_bsum, grid_for(r2 * r2), dim3(256), 0, s, r, a);
   const size_t lds = (size_t)2 * r * (r + 1) * sizeof(double);
-  hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(&k_ny_sub),
-                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-  if (e != hipSuccess) return e;
+  for (const void *k : {reinterpret_cast<const void *>(&k_ny_bsum), reinterpret_cast<const void *>(&k_ny_sub)}) {
+    hipError_t e = hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
+  }
+  hipLaunchKernelGGL(k_ny_bsum, dim3((unsigned)r2), dim3(256), lds, s, r, a);
   hipLaunchKernelGGL(k_ny_sub, dim3((unsigned)r2), dim3(256), lds, s, r, a);
   return hipGetLastError();
 }
