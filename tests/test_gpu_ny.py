@@ -16,6 +16,9 @@ test_oracle_ny.py).
   NY residual equals the closed form of the Valdemoro one.
 * Rejected combinations: FP32 / split BF16, the adjoint, the quadratic
   control, the batched residual, sigma entries other than +1 / -1.
+* Edges: r = 2 and 3; the step with the active-active mask on the
+  general-size kernels; the update map on an anti-Hermitian direction that is
+  not a residual.
 """
 import numpy as np
 import pytest
@@ -196,3 +199,75 @@ def test_ny_rejected_combinations(acse):
         assert abs(n2 - o[2]) <= 1e-10 * o[2]
     finally:
         ctx.close()
+
+
+@pytest.mark.parametrize("r,N", [(2, 2), (3, 4)])
+def test_ny_smallest_sizes(acse, r, N):
+    p = correlated(r, N, 20 + r)
+    sig = sigma_of(p, "prefix")
+    print(f"[ny] residual r={r} N={N}", flush=True)
+    oaa, oab, on2 = ost.residual(p["h"], p["V"], N, p["gamma"], p["d2aa"], p["d2ab"], sigma=sig)
+    ctx = acse.Context(r_max=r)
+    try:
+        Raa, Rab, n2 = ctx.residual(p["h"], p["V"], p["gamma"], p["d2aa"], p["d2ab"], N // 2, sigma=True)
+    finally:
+        ctx.close()
+    scale = max(np.abs(oaa).max(), np.abs(oab).max())
+    assert np.abs(Raa.cpu().numpy() - oaa).max() <= 1e-10 * scale
+    assert np.abs(Rab.cpu().numpy() - oab).max() <= 1e-10 * scale
+    assert abs(n2 - on2) <= 1e-10 * on2
+
+
+def test_ny_step_active_mask_and_general_kernels(acse):
+    """The NY step with the active-active mask, on the general-size kernels
+    (the one-index transforms, stored G2, row-chunked assembly), against the
+    oracle step with the same mask."""
+    r, N = 10, 8
+    p = correlated(r, N, 31)
+    sig = np.array([1, -1, 1, 1, -1, 1, -1, 1, -1, -1], dtype=float)
+    act = np.zeros(r, bool)
+    act[2:7] = True
+    print(f"[ny] step r={r} active={act.astype(int).tolist()} general kernels", flush=True)
+    o = ost.step(p["h"], p["V"], N, p["gamma"], p["d2aa"], p["d2ab"], 1e-3, active=act, sigma=sig)
+    ctx = acse.Context(r_max=r)
+    try:
+        g = ctx.step(p["h"], p["V"], p["gamma"], p["d2aa"], p["d2ab"], N // 2, eps=1e-3, return_ru=True,
+                     active=act, flags=acse.FLAG_GENERAL_KERNELS, sigma=[int(x) for x in sig])
+        for key in ("R_aa", "R_ab", "U_aa", "U_ab", "d2aa", "d2ab"):
+            x = g[key].cpu().numpy()
+            assert np.abs(x - o[key]).max() <= 1e-10 * np.abs(o[key]).max(), key
+        assert abs(g["energy"] - o["energy"]) <= 1e-12 * abs(o["energy"])
+    finally:
+        ctx.close()
+
+
+def test_ny_update_map_random_x(acse):
+    """acse_update_map with the NY 3-RDM on an anti-Hermitian direction that is
+    not a residual (X_aa antisymmetric in each pair, both blocks pair-exchange
+    symmetric and anti-Hermitian), against the oracle's anti-Hermitian branch."""
+    import torch
+    from oracle import residual as rs
+    r, N = 7, 6
+    p = correlated(r, N, 41)
+    sig = sigma_of(p, "prefix")
+    rng = np.random.default_rng(42)
+    x = rng.normal(size=(r, r, r, r))
+    xaa = x - x.transpose(1, 0, 2, 3) - x.transpose(0, 1, 3, 2) + x.transpose(1, 0, 3, 2)
+    xaa = xaa - xaa.transpose(2, 3, 0, 1)
+    x = rng.normal(size=(r, r, r, r))
+    xab = x + x.transpose(1, 0, 3, 2)
+    xab = xab - xab.transpose(2, 3, 0, 1)
+    print(f"[ny] update map r={r}", flush=True)
+    d1, d2 = rdm.blocks_to_spin_orbital(p["gamma"], p["d2aa"], p["d2ab"])
+    _, Xso = rdm.blocks_to_spin_orbital(np.eye(r), xaa, xab)
+    U = rs.residual_map(Xso, d1, d2, hermitian=False, sigma_so=rdm.sigma_spin_orbital(sig)).numpy()
+    uaa, uab = rdm.spin_orbital_to_blocks(U)
+    ctx = acse.Context(r_max=r)
+    try:
+        gaa, gab = ctx.update_map(p["h"], p["V"], p["gamma"], p["d2aa"], p["d2ab"], N // 2,
+                                  torch.from_numpy(xaa), torch.from_numpy(xab), sigma=True)
+    finally:
+        ctx.close()
+    scale = max(np.abs(uaa).max(), np.abs(uab).max())
+    assert np.abs(gaa.cpu().numpy() - uaa).max() <= 1e-10 * scale
+    assert np.abs(gab.cpu().numpy() - uab).max() <= 1e-10 * scale
