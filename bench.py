@@ -216,14 +216,15 @@ def bench_solve(acse, ctx, prob, work, pristine, torch, controls, iters, eps, st
 NY_BLOCK_GEMMS = 28  # spatial-block products of the NY share per map (the plan of ny_plan.h)
 
 
-def bench_ny(acse, ctx, prob, work, pristine, torch, stream, steps, warmup, eps, v_step_ms):
+def bench_ny(acse, ctx, prob, work, pristine, torch, stream, steps, warmup, eps, v_step_ms, mode="fp64"):
     """One acse_step with the Nakatsuji-Yasuda 3-RDM (Eq. (8)) on the same
-    workload, FP64: ms per step, the stage split with the NY share's own
-    stage, and the share's rate in issued block-GEMM flops (28 products of
-    2 r^6 per map) per second of its stage (permutations, cumulant blocks and
-    the combination included).  The check is E1 - E0 = -eps ||R||^2."""
+    workload, block products in `mode`: ms per step, the stage split with the
+    NY share's own stage, and the share's rate in issued block-GEMM flops (28
+    products of 2 r^6 per map) per second of its stage (permutations,
+    cumulant blocks and the combination included).  The check is
+    E1 - E0 = -eps ||R||^2."""
     r = prob.r
-    opts = acse.Context.options("fp64", sigma=True)
+    opts = acse.Context.options(mode, sigma=True)
 
     def restore():
         for w, q in zip(work, pristine):
@@ -412,9 +413,10 @@ def main():
         line["solve"] = bench_solve(acse, ctx, prob, work, pristine, torch, args.solve_controls.split(","),
                                     args.solve_iters, args.solve_eps, results.get("fp64", hr)["ms_per_step"])
     if args.ny_steps > 0:
-        line["nakatsuji_yasuda"] = bench_ny(acse, ctx, prob, work, pristine, torch, stream, args.ny_steps,
-                                            min(args.warmup, 2), args.eps,
-                                            results.get("fp64", hr)["ms_per_step"])
+        line["nakatsuji_yasuda"] = {
+            mode: bench_ny(acse, ctx, prob, work, pristine, torch, stream, args.ny_steps, min(args.warmup, 2),
+                           args.eps, results[mode]["ms_per_step"], mode)
+            for mode in args.modes.split(",")}
     if args.vjp_modes:
         line["vjp"] = bench_vjp(acse, gen, torch, args.vjp_modes.split(","), max(3, args.steps // 2),
                                 args.warmup)

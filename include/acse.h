@@ -113,12 +113,16 @@ typedef struct {
  *   ACSE_RECON_NY  Nakatsuji-Yasuda: the 3-cumulant is approximated by the
  *                  sigma-weighted, antisymmetrised product of two 2-cumulants
  *                  of Eq. (8) (App. D, NY part), never formed.  Both maps of
- *                  a step use it.  Its share runs as 28 spatial-block FP64
- *                  GEMMs of r^2 x r^2 x r^2 per map (a spin-orbital contraction
- *                  split over the spins of its internal indices), so it is
- *                  FP64 only: another precision is ACSE_ERR_UNSUPPORTED, as are
- *                  the adjoint (acse_residual_vjp), the quadratic step control
- *                  of acse_solve (which needs it) and the batched residual. */
+ *                  a step use it.  Its share runs as 28 spatial-block GEMMs
+ *                  of r^2 x r^2 x r^2 per map (a spin-orbital contraction split
+ *                  over the spins of its internal indices) in the call's
+ *                  precision; its combination into the map is FP64.  The
+ *                  first NY call allocates its workspace for r_max (about
+ *                  (19 r^4 + 44 r^4-sized operand buffers) x 8 bytes: 3.3 GB at
+ *                  r_max = 50; ACSE_ERR_NOMEM if that fails).  The adjoint
+ *                  (acse_residual_vjp), the quadratic step control of
+ *                  acse_solve (which needs it) and the batched residual are
+ *                  ACSE_ERR_UNSUPPORTED with it. */
 typedef enum { ACSE_RECON_V = 0, ACSE_RECON_NY = 1 } acse_reconstruction;
 
 /* acse_options.flags: run the general-size kernels at every r (the one-index

@@ -245,8 +245,6 @@ acse_status validate(acse_ctx c, const acse_problem *p, const acse_options *o, b
     if (o->reconstruction != ACSE_RECON_V && o->reconstruction != ACSE_RECON_NY)
       return fail(c, ACSE_ERR_ARG, "unknown reconstruction");
     if (o->reconstruction == ACSE_RECON_NY) {
-      if (o->precision != ACSE_FP64)
-        return fail(c, ACSE_ERR_UNSUPPORTED, "the Nakatsuji-Yasuda reconstruction is built for FP64 only");
       if (o->ny_sigma)
         for (int q = 0; q < p->r; ++q)
           if (o->ny_sigma[q] != 1 && o->ny_sigma[q] != -1)
@@ -422,15 +420,20 @@ int map_cfg(acse_ctx c, GemmPrec prec, int r, int cfg) {
 }
 
 // Nakatsuji-Yasuda workspace, sized for r_max: the seven source blocks and
-// the nine product blocks (natural r^4), the operand buffers of the plan, Y
-// and sigma.  Operand buffers are cleared whenever r changes (their padding
-// rows and columns must read as zero; the GEMMs and permutations write only
-// the r^2 x r^2 part of the intermediates).
+// the nine product blocks (natural r^4), the operand buffers of the plan, an
+// FP64 staging buffer per intermediate (FP32 / split-BF16 products write
+// their first-stage results there, then one pass converts them to operand
+// format), Y and sigma.  Operand buffers are cleared whenever r changes (their
+// padding rows and columns must read as zero; the GEMMs and permutations
+// write only the r^2 x r^2 part of the intermediates).
 constexpr int kNySrc = 7, kNyProd = 12;  // 9 products + the 3 blocks of B
 struct NyPtrs {
   double *src[kNySrc], *prod[kNyProd], *Y, *sig;
   std::vector<double *> buf;
+  std::map<int, double *> staging;  // intermediate operand buffer id -> FP64 staging
 };
+
+int64_t ny_num_bufs(const ny::Plan &P) { return (int64_t)P.num_bufs + (int64_t)P.inter_buf.size(); }
 
 NyPtrs ny_carve(acse_ctx c, int r) {
   NyPtrs q{};
@@ -444,6 +447,7 @@ NyPtrs ny_carve(acse_ctx c, int r) {
   q.sig = reinterpret_cast<double *>(p); p += round_up(rm * 8, 256);
   q.buf.resize(c->ny_plan.num_bufs);
   for (int k = 0; k < c->ny_plan.num_bufs; ++k) { q.buf[k] = reinterpret_cast<double *>(p); p += opb; }
+  for (const auto &kv : c->ny_plan.inter_buf) { q.staging[kv.second] = reinterpret_cast<double *>(p); p += opb; }
   return q;
 }
 
@@ -456,7 +460,7 @@ acse_status ensure_ny_ws(acse_ctx c) {
   const int64_t rm = c->r_max;
   const int64_t nat = round_up(rm * rm * rm * rm * 8, 256);
   const int64_t bytes = (kNySrc + kNyProd) * nat + round_up(rm * rm * 8, 256) + round_up(rm * 8, 256) +
-                        (int64_t)c->ny_plan.num_bufs * c->op_bytes;
+                        ny_num_bufs(c->ny_plan) * c->op_bytes;
   if (hipMalloc(&c->nybase, bytes) != hipSuccess) {
     (void)hipGetLastError();
     c->nybase = nullptr;
@@ -469,7 +473,7 @@ acse_status ensure_ny_ws(acse_ctx c) {
 
 // The NY share of F(X): S_aa -= C_aa, S_ab -= C_ab (C = B - B(k<->l), B the
 // 3-cumulant's share of the 3-RDM contraction), on the plan of ny_plan.h.
-acse_status ny_share(acse_ctx c, const acse_problem *p, const double *Xaa, const double *Xab,
+acse_status ny_share(acse_ctx c, const acse_problem *p, GemmPrec prec, const double *Xaa, const double *Xab,
                      double *Saa, double *Sab) {
   const int r = p->r;
   hipStream_t s = c->stream;
@@ -482,7 +486,7 @@ acse_status ny_share(acse_ctx c, const acse_problem *p, const double *Xaa, const
   bool upload = c->ny_sigma_dev_copy != c->ny_sigma;
   if (c->ny_r != r) {
     const int64_t opb = round_up(rows * ld * 8, 256);
-    HIP_TRY(c, launch_fill((int64_t)P.num_bufs * opb / 8, 0.0, q.buf[0], s));
+    HIP_TRY(c, launch_fill(ny_num_bufs(P) * opb / 8, 0.0, q.buf[0], s));
     c->ny_r = r;
     upload = true;
   }
@@ -496,6 +500,11 @@ acse_status ny_share(acse_ctx c, const acse_problem *p, const double *Xaa, const
   HIP_TRY(c, launch_ny_sources(r, p->d1, p->d2aa, p->d2ab, Xab, q.sig, q.src, s));
   const double *src[3][3] = {{Xaa, Xab, q.src[6]}, {q.src[0], q.src[1], q.src[2]}, {q.src[3], q.src[4], q.src[5]}};
   auto slot = [](int block) { return block == 0 ? 0 : block == 5 ? 1 : 2; };
+  auto opref = [&](int id) {
+    OperandRef o{q.buf[id], nullptr};
+    if (prec == GEMM_BF16X3) o.lo = reinterpret_cast<char *>(q.buf[id]) + rows * ld * 2;
+    return o;
+  };
   const int64_t nst[4] = {r2 * r, r2, r, 1};
   for (const ny::PermOp &op : P.perms) {
     PermArgs a{};
@@ -508,7 +517,7 @@ acse_status ny_share(acse_ctx c, const acse_problem *p, const double *Xaa, const
     a.src2 = nullptr;
     a.c2 = 0.0;
     a.accumulate = 0;
-    HIP_TRY(c, launch_permute4(GEMM_F64, a, OperandRef{q.buf[op.buf], nullptr}, s));
+    HIP_TRY(c, launch_permute4(prec, a, opref(op.buf), s));
   }
   // GEMMs in two phases (the first-stage products, then the second stages
   // that read them); within a phase the t-th terms of all output blocks go out
@@ -516,9 +525,23 @@ acse_status ny_share(acse_ctx c, const acse_problem *p, const double *Xaa, const
   // holds several r^2 x r^2 products and fills the chip
   int ns = 0;
   const ny::Stage *stg = ny::stages(&ns);
-  const int cfg = map_cfg(c, GEMM_F64, r, -1);
-  const int kp = gemm_kp(GEMM_F64, (int)r2, (int)ld);
+  const int cfg = map_cfg(c, prec, r, -1);
+  const int kp = gemm_kp(prec, (int)r2, (int)ld);
+  const bool f64 = prec == GEMM_F64;
   for (int phase = 0; phase < 2; ++phase) {
+    if (phase == 1 && !f64) {
+      // first-stage results (FP64) into the precision's operand format
+      for (const auto &kv : q.staging) {
+        PermArgs a{};
+        a.r = r;
+        a.rows = rows;
+        a.ld = ld;
+        a.src1 = kv.second;
+        a.s1[0] = r * ld; a.s1[1] = ld; a.s1[2] = r; a.s1[3] = 1;
+        a.c1 = 1.0;
+        HIP_TRY(c, launch_permute4(prec, a, opref(kv.first), s));
+      }
+    }
     for (int term = 0;; ++term) {
       std::vector<const ny::GemmOp *> round;
       for (const ny::GemmOp &g : P.gemms)
@@ -533,20 +556,25 @@ acse_status ny_share(acse_ctx c, const acse_problem *p, const double *Xaa, const
           ny::gemm_out_strides(stg[g.stage], r, ld, os);
           GemmProb &G = batch.p[k];
           G = GemmProb{};
-          G.A = q.buf[g.a_buf];
-          G.B = q.buf[g.b_buf];
-          G.C = ny::is_product(g.out) ? q.prod[P.product_nat.at({g.out, g.block})]
-                                      : q.buf[P.inter_buf.at({g.out, g.block})];
+          const OperandRef ra = opref(g.a_buf), rb = opref(g.b_buf);
+          G.A = ra.hi; G.A2 = ra.lo; G.B = rb.hi; G.B2 = rb.lo;
+          if (ny::is_product(g.out)) {
+            G.C = q.prod[P.product_nat.at({g.out, g.block})];
+          } else {
+            const int id = P.inter_buf.at({g.out, g.block});
+            G.C = f64 ? q.buf[id] : q.staging.at(id);
+          }
           G.alpha = g.alpha;
           G.M = (int)r2; G.N = (int)r2; G.Kp = kp; G.ld = (int)ld; G.rdiv = r;
           G.sm1 = os[0]; G.sm0 = os[1]; G.sn1 = os[2]; G.sn0 = os[3];
           G.ksplit = 1; G.kchunk = kp; G.accumulate = g.accumulate;
         }
-        HIP_TRY(c, gemm_launch(GEMM_F64, cfg, batch, s));
+        HIP_TRY(c, gemm_launch(prec, cfg, batch, s));
       }
     }
   }
-  HIP_TRY(c, launch_ny_trace_y(r, ld, q.buf[P.inter_buf.at({ny::T_W, 0})], q.buf[P.inter_buf.at({ny::T_W, 5})],
+  const int w0 = P.inter_buf.at({ny::T_W, 0}), w5 = P.inter_buf.at({ny::T_W, 5});
+  HIP_TRY(c, launch_ny_trace_y(r, ld, f64 ? q.buf[w0] : q.staging.at(w0), f64 ? q.buf[w5] : q.staging.at(w5),
                                q.Y, s));
   NyCombineArgs a{};
   const int pblk[3] = {0, 5, 6};
@@ -569,7 +597,8 @@ acse_status ny_share(acse_ctx c, const acse_problem *p, const double *Xaa, const
 // reconstruction its share joins the assembled sum before the exchange.
 acse_status map_back(acse_ctx c, const acse_problem *p, double sigma, double *Oaa, double *Oab,
                      const ActiveBits &act, double *Maa, double *Mab, double *norm_out,
-                     Workspace &w, const double *Xaa = nullptr, const double *Xab = nullptr) {
+                     Workspace &w, const double *Xaa = nullptr, const double *Xab = nullptr,
+                     GemmPrec prec = GEMM_F64) {
   const int r = p->r;
   hipStream_t s = c->stream;
   {
@@ -579,7 +608,7 @@ acse_status map_back(acse_ctx c, const acse_problem *p, double sigma, double *Oa
   }
   if (c->ny_on) {
     if (!Xaa || !Xab) return fail(c, ACSE_ERR_UNSUPPORTED, "the NY share needs the map's X");
-    acse_status st = ny_share(c, p, Xaa, Xab, w.Saa, w.Sab);
+    acse_status st = ny_share(c, p, prec, Xaa, Xab, w.Saa, w.Sab);
     if (st != ACSE_OK) return st;
   }
   StageTimer t4b(c, 4);
@@ -611,7 +640,7 @@ acse_status run_map(acse_ctx c, const acse_problem *p, GemmPrec prec, int cfg, c
     StageTimer t3(c, 3);
     HIP_TRY(c, gemm_launch(prec, use_cfg, batch, c->stream));
   }
-  return map_back(c, p, sigma, Oaa, Oab, act, Maa, Mab, w.scal + slot, w, Xaa, Xab);
+  return map_back(c, p, sigma, Oaa, Oab, act, Maa, Mab, w.scal + slot, w, Xaa, Xab, prec);
 }
 
 ActiveBits make_bits(const acse_options *o, int r, bool *any) {

@@ -14,8 +14,11 @@ test_oracle_ny.py).
   -eps ||R||^2 and Tr U = 0 per block, and the share is nonzero.
 * r = 96 (the largest r): a closed-shell determinant has 2Delta = 0, so the
   NY residual equals the closed form of the Valdemoro one.
-* Rejected combinations: FP32 / split BF16, the adjoint, the quadratic
-  control, the batched residual, sigma entries other than +1 / -1.
+* FP32 and split-BF16 block products (the combination FP64) at the bars of
+  the Valdemoro mixed modes, 1e-5 and 5e-5 of the largest element, on the
+  residual and on the step's update.
+* Rejected combinations: the adjoint, the quadratic control, the batched
+  residual, sigma entries other than +1 / -1.
 * Edges: r = 2 and 3; the step with the active-active mask on the
   general-size kernels; the update map on an anti-Hermitian direction that is
   not a residual.
@@ -180,9 +183,6 @@ def test_ny_rejected_combinations(acse):
     p = correlated(4, 4, 0)
     ctx = acse.Context(r_max=4)
     try:
-        for prec in ("fp32", "bf16x3"):
-            with pytest.raises(acse.AcseError, match="FP64 only"):
-                ctx.residual(p["h"], p["V"], p["gamma"], p["d2aa"], p["d2ab"], 2, precision=prec, sigma=True)
         with pytest.raises(acse.AcseError, match="ny_sigma"):
             ctx.residual(p["h"], p["V"], p["gamma"], p["d2aa"], p["d2ab"], 2, sigma=[1, 0, -1, -1])
         with pytest.raises(acse.AcseError, match="quadratic"):
@@ -271,3 +271,29 @@ def test_ny_update_map_random_x(acse):
     scale = max(np.abs(uaa).max(), np.abs(uab).max())
     assert np.abs(gaa.cpu().numpy() - uaa).max() <= 1e-10 * scale
     assert np.abs(gab.cpu().numpy() - uab).max() <= 1e-10 * scale
+
+
+@pytest.mark.parametrize("precision,tol", [("fp32", 1e-5), ("bf16x3", 5e-5)])
+def test_ny_mixed_precision(acse, precision, tol):
+    r, N = 16, 10
+    p = correlated(r, N, 51)
+    sig = sigma_of(p, "prefix")
+    print(f"[ny] step r={r} precision={precision}", flush=True)
+    o = ost.step(p["h"], p["V"], N, p["gamma"], p["d2aa"], p["d2ab"], 1e-3, sigma=sig)
+    ctx = acse.Context(r_max=r)
+    try:
+        g = ctx.step(p["h"], p["V"], p["gamma"], p["d2aa"], p["d2ab"], N // 2, eps=1e-3, return_ru=True,
+                     precision=precision, sigma=True)
+        for key in ("R_aa", "R_ab", "U_aa", "U_ab"):
+            x = g[key].cpu().numpy()
+            assert np.abs(x - o[key]).max() <= tol * np.abs(o[key]).max(), key
+        assert abs(g["norm2"] - o["norm2"]) <= tol * o["norm2"]
+        # the share itself at the same relative bar
+        vaa, vab, _ = ost.residual(p["h"], p["V"], N, p["gamma"], p["d2aa"], p["d2ab"])
+        share = max(np.abs(o["R_aa"] - vaa).max(), np.abs(o["R_ab"] - vab).max())
+        Vaa, Vab, _ = ctx.residual(p["h"], p["V"], p["gamma"], p["d2aa"], p["d2ab"], N // 2, precision=precision)
+        got = max(np.abs((g["R_aa"] - Vaa).cpu().numpy() - (o["R_aa"] - vaa)).max(),
+                  np.abs((g["R_ab"] - Vab).cpu().numpy() - (o["R_ab"] - vab)).max())
+        assert got <= 10 * tol * share
+    finally:
+        ctx.close()
