@@ -10,8 +10,12 @@ test_oracle_ny.py).
   Valdemoro part.
 * One Euler step (both maps with the NY 3-RDM) and the Euler driver with the
   fixed control, against the oracle's step and iteration.
-* r = 50 (the headline size): the identities that hold at any size, E1 - E0 =
-  -eps ||R||^2 and Tr U = 0 per block, and the share is nonzero.
+* r = 50 (the headline size): the residual in the launch configuration the
+  bench times (autotuned tile), every precision, against the stored oracle
+  values of tests/golden/r50_ny_residual.json (sampled elements, block norms,
+  ||R||^2; written by tests/golden/make_golden_ny.py, which calls only the
+  oracle); and the identities that hold at any size, E1 - E0 = -eps ||R||^2
+  and Tr U = 0 per block.
 * r = 96 (the largest r): a closed-shell determinant has 2Delta = 0, so the
   NY residual equals the closed form of the Valdemoro one.
 * FP32 and split-BF16 block products (the combination FP64) at the bars of
@@ -23,6 +27,9 @@ test_oracle_ny.py).
   general-size kernels; the update map on an anti-Hermitian direction that is
   not a residual.
 """
+import json
+import os
+
 import numpy as np
 import pytest
 
@@ -295,5 +302,32 @@ def test_ny_mixed_precision(acse, precision, tol):
         got = max(np.abs((g["R_aa"] - Vaa).cpu().numpy() - (o["R_aa"] - vaa)).max(),
                   np.abs((g["R_ab"] - Vab).cpu().numpy() - (o["R_ab"] - vab)).max())
         assert got <= 10 * tol * share
+    finally:
+        ctx.close()
+
+
+GOLDEN_NY = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "r50_ny_residual.json")
+
+
+@pytest.mark.parametrize("precision,tol", [("fp64", 1e-10), ("fp32", 1e-5), ("bf16x3", 5e-5)])
+def test_ny_r50_residual_vs_stored_oracle(acse, precision, tol):
+    g = json.load(open(GOLDEN_NY))
+    p = gen.named(g["workload"])
+    r, N = p["r"], p["N"]
+    assert r == g["r"] == 50 and N == g["N"]
+    print(f"[ny] r=50 residual vs stored oracle, precision={precision}", flush=True)
+    ctx = acse.Context(r_max=r)
+    try:
+        prob, _ = ctx.problem(p["h"], p["V"], p["gamma"], p["d2aa"], p["d2ab"], N // 2)
+        ctx.autotune_raw(prob, ctx.options(precision))
+        Raa, Rab, n2 = ctx.residual(p["h"], p["V"], p["gamma"], p["d2aa"], p["d2ab"], N // 2,
+                                    precision=precision, sigma=True)
+        idx = tuple(np.array(g["index"]).T)
+        for key, got in (("R_aa", Raa), ("R_ab", Rab)):
+            ref = np.array(g["samples"][key])
+            x = got.cpu().numpy()
+            assert np.abs(x[idx] - ref).max() <= tol * np.abs(ref).max(), key
+            assert abs(float(np.linalg.norm(x)) - g["norms"][key]) <= tol * g["norms"][key], key
+        assert abs(n2 - g["norm2"]) <= tol * g["norm2"]
     finally:
         ctx.close()
