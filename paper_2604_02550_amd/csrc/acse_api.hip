@@ -105,6 +105,9 @@ struct acse_ctx_s {
   void *nybase = nullptr;
   int64_t nybytes = 0;
   int ny_r = 0;                     // r the operand buffers were last cleared for
+  // set by acse_step around its update map: the 2-RDM has not changed since
+  // the residual map, whose cumulant blocks and their operand layouts stand
+  bool ny_reuse_d = false;
 };
 
 namespace {
@@ -496,8 +499,10 @@ acse_status ny_share(acse_ctx c, const acse_problem *p, GemmPrec prec, const dou
     c->ny_sigma_dev_copy = c->ny_sigma;
     HIP_TRY(c, hipMemcpyAsync(q.sig, c->ny_sigma_dev_copy.data(), r * sizeof(double), hipMemcpyHostToDevice, s));
   }
-  // sources: X blocks 0000 / 0101 / 0110, then D and sigma D
-  HIP_TRY(c, launch_ny_sources(r, p->d1, p->d2aa, p->d2ab, Xab, q.sig, q.src, s));
+  // sources: X blocks 0000 / 0101 / 0110, then D and sigma D (kept from the
+  // previous map of the same step when the 2-RDM has not changed)
+  const bool keep_d = c->ny_reuse_d && !upload;
+  HIP_TRY(c, launch_ny_sources(r, p->d1, p->d2aa, p->d2ab, Xab, q.sig, q.src, keep_d, s));
   const double *src[3][3] = {{Xaa, Xab, q.src[6]}, {q.src[0], q.src[1], q.src[2]}, {q.src[3], q.src[4], q.src[5]}};
   auto slot = [](int block) { return block == 0 ? 0 : block == 5 ? 1 : 2; };
   auto opref = [&](int id) {
@@ -507,6 +512,7 @@ acse_status ny_share(acse_ctx c, const acse_problem *p, GemmPrec prec, const dou
   };
   const int64_t nst[4] = {r2 * r, r2, r, 1};
   for (const ny::PermOp &op : P.perms) {
+    if (keep_d && op.src != ny::T_X) continue;
     PermArgs a{};
     a.r = r;
     a.rows = rows;
@@ -925,10 +931,12 @@ acse_status acse_step(acse_ctx ctx, acse_problem *prob, double eps, const acse_o
   if ((st = run_map(ctx, prob, prec, cfg, w.Aaa, w.Aab, -1.0, Raa, Rab, act,
                     masked ? w.Maa : nullptr, masked ? w.Mab : nullptr, 0)) != ACSE_OK)
     return st;
-  // U = F(R_m)
-  if ((st = run_map(ctx, prob, prec, cfg, masked ? w.Maa : Raa, masked ? w.Mab : Rab, +1.0, Uaa, Uab,
-                    ActiveBits{}, nullptr, nullptr, 2)) != ACSE_OK)
-    return st;
+  // U = F(R_m), on the same 2-RDM
+  ctx->ny_reuse_d = ctx->ny_on;
+  st = run_map(ctx, prob, prec, cfg, masked ? w.Maa : Raa, masked ? w.Mab : Rab, +1.0, Uaa, Uab,
+               ActiveBits{}, nullptr, nullptr, 2);
+  ctx->ny_reuse_d = false;
+  if (st != ACSE_OK) return st;
   // 2D <- 2D + eps U, trace restoration, 1-RDM contraction, energy (FP64)
   {
     StageTimer t5(ctx, 5);

@@ -9,9 +9,11 @@ namespace acse {
 // Canonical spin blocks of the 2-cumulant (Eq. (7)) and of X, natural r^4:
 //   Daa = d2aa - 1/2 (g_pr g_qs - g_ps g_qr),  Dab = d2ab - 1/2 g_pr g_qs,
 //   Dabx[p,q,r,s] = -Dab[p,q,s,r],  SD* = sigma_r D* (third index scaled),
-//   Xabx[p,q,r,s] = -Xab[p,q,s,r].
+//   Xabx[p,q,r,s] = -Xab[p,q,s,r].  With keep_d only Xabx is written (the
+// cumulant blocks stand from a previous call on the same 2-RDM).
 hipError_t launch_ny_sources(int r, const double *g, const double *d2aa, const double *d2ab,
-                             const double *Xab, const double *sigma, double *const src[7], hipStream_t s);
+                             const double *Xab, const double *sigma, double *const src[7], bool keep_d,
+                             hipStream_t s);
 // Y[k,a] = sum_p (W0 + W5)[(p r + k) ld + p r + a] (the alpha-alpha block of
 // the partial trace of the first intermediate of T_il).
 hipError_t launch_ny_trace_y(int r, int64_t ld, const double *W0, const double *W5, double *Y, hipStream_t s);

@@ -14,7 +14,7 @@ k_ny_sources(int r, const double *__restrict__ g, const double *__restrict__ d2a
              const double *__restrict__ d2ab, const double *__restrict__ Xab,
              const double *__restrict__ sig, double *__restrict__ Daa, double *__restrict__ Dab,
              double *__restrict__ Dabx, double *__restrict__ SDaa, double *__restrict__ SDab,
-             double *__restrict__ SDabx, double *__restrict__ Xabx) {
+             double *__restrict__ SDabx, double *__restrict__ Xabx, int keep_d) {
   const int64_t r2 = (int64_t)r * r;
   const int64_t e = tid64();
   if (e >= r2 * r2) return;
@@ -25,6 +25,8 @@ k_ny_sources(int r, const double *__restrict__ g, const double *__restrict__ d2a
   const int q = (int)(t % r);
   const int p = (int)(t / r);
   const int64_t ex = ((int64_t)(p * r + q) * r + s) * r + c;  // [p,q,s,c]
+  Xabx[e] = -Xab[ex];
+  if (keep_d) return;
   const double gpc = g[p * r + c], gqs = g[q * r + s], gps = g[p * r + s], gqc = g[q * r + c];
   const double daa = d2aa[e] - 0.5 * (gpc * gqs - gps * gqc);
   const double dab = d2ab[e] - 0.5 * gpc * gqs;
@@ -36,7 +38,6 @@ k_ny_sources(int r, const double *__restrict__ g, const double *__restrict__ d2a
   SDaa[e] = sg * daa;
   SDab[e] = sg * dab;
   SDabx[e] = sg * dabx;
-  Xabx[e] = -Xab[ex];
 }
 
 __global__ void __launch_bounds__(256)
@@ -105,10 +106,11 @@ __global__ void __launch_bounds__(256) k_ny_sub(int r, NyCombineArgs a) {
 }  // namespace
 
 hipError_t launch_ny_sources(int r, const double *g, const double *d2aa, const double *d2ab,
-                             const double *Xab, const double *sigma, double *const src[7], hipStream_t s) {
+                             const double *Xab, const double *sigma, double *const src[7], bool keep_d,
+                             hipStream_t s) {
   const int64_t n = (int64_t)r * r * r * r;
   hipLaunchKernelGGL(k_ny_sources, grid_for(n), dim3(256), 0, s, r, g, d2aa, d2ab, Xab, sigma, src[0],
-                     src[1], src[2], src[3], src[4], src[5], src[6]);
+                     src[1], src[2], src[3], src[4], src[5], src[6], keep_d ? 1 : 0);
   return hipGetLastError();
 }
 
