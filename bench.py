@@ -213,7 +213,7 @@ def bench_solve(acse, ctx, prob, work, pristine, torch, controls, iters, eps, st
     return res
 
 
-NY_BLOCK_GEMMS = 28  # spatial-block products of the NY share per map (the plan of ny_plan.h)
+NY_BLOCK_GEMMS = 18  # spatial-block products of the NY share per map (the plan of ny_plan.h)
 
 
 def bench_ny(acse, ctx, prob, work, pristine, torch, stream, steps, warmup, eps, v_step_ms, mode="fp64"):

@@ -113,7 +113,7 @@ typedef struct {
  *   ACSE_RECON_NY  Nakatsuji-Yasuda: the 3-cumulant is approximated by the
  *                  sigma-weighted, antisymmetrised product of two 2-cumulants
  *                  of Eq. (8) (App. D, NY part), never formed.  Both maps of
- *                  a step use it.  Its share runs as 28 spatial-block GEMMs
+ *                  a step use it.  Its share runs as 18 spatial-block GEMMs
  *                  of r^2 x r^2 x r^2 per map (a spin-orbital contraction split
  *                  over the spins of its internal indices) in the call's
  *                  precision; its combination into the map is FP64.  The

@@ -432,11 +432,11 @@ int map_cfg(acse_ctx c, GemmPrec prec, int r, int cfg) {
 constexpr int kNySrc = 7, kNyProd = 12;  // 9 products + the 3 blocks of B
 struct NyPtrs {
   double *src[kNySrc], *prod[kNyProd], *Y, *sig;
-  std::vector<double *> buf;
-  std::map<int, double *> staging;  // intermediate operand buffer id -> FP64 staging
+  std::vector<double *> buf;      // operand buffers
+  std::vector<double *> staging;  // FP64 intermediates, in their next stage's operand layout
 };
 
-int64_t ny_num_bufs(const ny::Plan &P) { return (int64_t)P.num_bufs + (int64_t)P.inter_buf.size(); }
+int64_t ny_num_bufs(const ny::Plan &P) { return (int64_t)P.num_bufs + (int64_t)P.staging.size(); }
 
 NyPtrs ny_carve(acse_ctx c, int r) {
   NyPtrs q{};
@@ -450,7 +450,8 @@ NyPtrs ny_carve(acse_ctx c, int r) {
   q.sig = reinterpret_cast<double *>(p); p += round_up(rm * 8, 256);
   q.buf.resize(c->ny_plan.num_bufs);
   for (int k = 0; k < c->ny_plan.num_bufs; ++k) { q.buf[k] = reinterpret_cast<double *>(p); p += opb; }
-  for (const auto &kv : c->ny_plan.inter_buf) { q.staging[kv.second] = reinterpret_cast<double *>(p); p += opb; }
+  q.staging.resize(c->ny_plan.staging.size());
+  for (size_t k = 0; k < q.staging.size(); ++k) { q.staging[k] = reinterpret_cast<double *>(p); p += opb; }
   return q;
 }
 
@@ -510,66 +511,64 @@ acse_status ny_share(acse_ctx c, const acse_problem *p, GemmPrec prec, const dou
     if (prec == GEMM_BF16X3) o.lo = reinterpret_cast<char *>(q.buf[id]) + rows * ld * 2;
     return o;
   };
+  auto stage_of = [&](int t, int b) { return q.staging[P.staging.at({t, b})]; };
   const int64_t nst[4] = {r2 * r, r2, r, 1};
-  for (const ny::PermOp &op : P.perms) {
-    if (keep_d && op.src != ny::T_X) continue;
-    PermArgs a{};
-    a.r = r;
-    a.rows = rows;
-    a.ld = ld;
-    a.src1 = src[op.src][slot(op.block)];
-    for (int t = 0; t < 4; ++t) a.s1[t] = nst[P.layout_strides[4 * op.layout + t]];
-    a.c1 = 1.0;
-    a.src2 = nullptr;
-    a.c2 = 0.0;
-    a.accumulate = 0;
-    HIP_TRY(c, launch_permute4(prec, a, opref(op.buf), s));
-  }
-  // GEMMs in two phases (the first-stage products, then the second stages
-  // that read them); within a phase the t-th terms of all output blocks go out
-  // together (distinct outputs), up to kMaxGemmProbs a launch, so a launch
-  // holds several r^2 x r^2 products and fills the chip
+  const int64_t pst[4] = {r * ld, ld, r, 1};  // staging: the operand layout in FP64
   int ns = 0;
   const ny::Stage *stg = ny::stages(&ns);
   const int cfg = map_cfg(c, prec, r, -1);
   const int kp = gemm_kp(prec, (int)r2, (int)ld);
-  const bool f64 = prec == GEMM_F64;
   for (int phase = 0; phase < 2; ++phase) {
-    if (phase == 1 && !f64) {
-      // first-stage results (FP64) into the precision's operand format
-      for (const auto &kv : q.staging) {
-        PermArgs a{};
-        a.r = r;
-        a.rows = rows;
-        a.ld = ld;
-        a.src1 = kv.second;
-        a.s1[0] = r * ld; a.s1[1] = ld; a.s1[2] = r; a.s1[3] = 1;
-        a.c1 = 1.0;
-        HIP_TRY(c, launch_permute4(prec, a, opref(kv.first), s));
+    // operands of this phase: source blocks permuted into operand layout, or
+    // intermediates converted from their FP64 staging; sums and differences
+    // of two blocks for the crosswise pairs
+    for (const ny::OperandBuild &o : P.operands) {
+      if (o.phase != phase) continue;
+      const bool src_op = ny::is_source(o.t1);
+      if (keep_d && src_op && o.t1 != ny::T_X) continue;
+      PermArgs a{};
+      a.r = r;
+      a.rows = rows;
+      a.ld = ld;
+      a.c1 = 1.0;
+      if (src_op) {
+        a.src1 = src[o.t1][slot(o.b1)];
+        for (int t = 0; t < 4; ++t) a.s1[t] = nst[P.layout_strides[4 * o.layout + t]];
+        if (o.t2 >= 0) {
+          a.src2 = src[o.t2][slot(o.b2)];
+          for (int t = 0; t < 4; ++t) a.s2[t] = a.s1[t];
+          a.c2 = o.c2;
+        }
+      } else {
+        a.src1 = stage_of(o.t1, o.b1);
+        for (int t = 0; t < 4; ++t) a.s1[t] = pst[t];
+        if (o.t2 >= 0) {
+          a.src2 = stage_of(o.t2, o.b2);
+          for (int t = 0; t < 4; ++t) a.s2[t] = pst[t];
+          a.c2 = o.c2;
+        }
       }
+      HIP_TRY(c, launch_permute4(prec, a, opref(o.buf), s));
     }
+    // products: the t-th terms of all output blocks of the phase go out
+    // together (distinct outputs), up to kMaxGemmProbs a launch
     for (int term = 0;; ++term) {
-      std::vector<const ny::GemmOp *> round;
-      for (const ny::GemmOp &g : P.gemms)
-        if ((g.stage >= ns / 2) == (phase == 1) && g.term == term) round.push_back(&g);
+      std::vector<const ny::Product *> round;
+      for (const ny::Product &g : P.products)
+        if (g.phase == phase && g.term == term) round.push_back(&g);
       if (round.empty()) break;
       for (size_t b0 = 0; b0 < round.size(); b0 += kMaxGemmProbs) {
         GemmBatch batch{};
         batch.count = (int)std::min<size_t>(kMaxGemmProbs, round.size() - b0);
         for (int k = 0; k < batch.count; ++k) {
-          const ny::GemmOp &g = *round[b0 + k];
+          const ny::Product &g = *round[b0 + k];
           int64_t os[4];
           ny::gemm_out_strides(stg[g.stage], r, ld, os);
           GemmProb &G = batch.p[k];
           G = GemmProb{};
           const OperandRef ra = opref(g.a_buf), rb = opref(g.b_buf);
           G.A = ra.hi; G.A2 = ra.lo; G.B = rb.hi; G.B2 = rb.lo;
-          if (ny::is_product(g.out)) {
-            G.C = q.prod[P.product_nat.at({g.out, g.block})];
-          } else {
-            const int id = P.inter_buf.at({g.out, g.block});
-            G.C = f64 ? q.buf[id] : q.staging.at(id);
-          }
+          G.C = ny::is_product(g.out) ? q.prod[P.product_nat.at({g.out, g.block})] : stage_of(g.out, g.block);
           G.alpha = g.alpha;
           G.M = (int)r2; G.N = (int)r2; G.Kp = kp; G.ld = (int)ld; G.rdiv = r;
           G.sm1 = os[0]; G.sm0 = os[1]; G.sn1 = os[2]; G.sn0 = os[3];
@@ -578,10 +577,17 @@ acse_status ny_share(acse_ctx c, const acse_problem *p, GemmPrec prec, const dou
         HIP_TRY(c, gemm_launch(prec, cfg, batch, s));
       }
     }
+    for (const ny::Unscramble &u : P.unscrambles) {
+      if (u.phase != phase) continue;
+      if (ny::is_product(u.out)) {
+        HIP_TRY(c, launch_ny_unscramble(r2 * r2, q.prod[P.product_nat.at({u.out, u.bx})],
+                                        q.prod[P.product_nat.at({u.out, u.by})], s));
+      } else {
+        HIP_TRY(c, launch_ny_unscramble(r2 * ld, stage_of(u.out, u.bx), stage_of(u.out, u.by), s));
+      }
+    }
   }
-  const int w0 = P.inter_buf.at({ny::T_W, 0}), w5 = P.inter_buf.at({ny::T_W, 5});
-  HIP_TRY(c, launch_ny_trace_y(r, ld, f64 ? q.buf[w0] : q.staging.at(w0), f64 ? q.buf[w5] : q.staging.at(w5),
-                               q.Y, s));
+  HIP_TRY(c, launch_ny_trace_y(r, ld, stage_of(ny::T_W, 0), stage_of(ny::T_W, 5), q.Y, s));
   NyCombineArgs a{};
   const int pblk[3] = {0, 5, 6};
   for (int b = 0; b < 3; ++b) {

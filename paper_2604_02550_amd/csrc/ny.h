@@ -14,6 +14,9 @@ namespace acse {
 hipError_t launch_ny_sources(int r, const double *g, const double *d2aa, const double *d2ab,
                              const double *Xab, const double *sigma, double *const src[7], bool keep_d,
                              hipStream_t s);
+// (x, y) <- ((x + y) / 2, (x - y) / 2) over n elements: the two blocks of a
+// crosswise pair from the products of the sums and of the differences.
+hipError_t launch_ny_unscramble(int64_t n, double *x, double *y, hipStream_t s);
 // Y[k,a] = sum_p (W0 + W5)[(p r + k) ld + p r + a] (the alpha-alpha block of
 // the partial trace of the first intermediate of T_il).
 hipError_t launch_ny_trace_y(int r, int64_t ld, const double *W0, const double *W5, double *Y, hipStream_t s);

@@ -40,6 +40,14 @@ k_ny_sources(int r, const double *__restrict__ g, const double *__restrict__ d2a
   SDabx[e] = sg * dabx;
 }
 
+__global__ void __launch_bounds__(256) k_ny_unscramble(int64_t n, double *__restrict__ x, double *__restrict__ y) {
+  const int64_t e = tid64();
+  if (e >= n) return;
+  const double a = x[e], b = y[e];
+  x[e] = 0.5 * (a + b);
+  y[e] = 0.5 * (a - b);
+}
+
 __global__ void __launch_bounds__(256)
 k_ny_trace_y(int r, int64_t ld, const double *__restrict__ W0, const double *__restrict__ W5,
              double *__restrict__ Y) {
@@ -111,6 +119,11 @@ hipError_t launch_ny_sources(int r, const double *g, const double *d2aa, const d
   const int64_t n = (int64_t)r * r * r * r;
   hipLaunchKernelGGL(k_ny_sources, grid_for(n), dim3(256), 0, s, r, g, d2aa, d2ab, Xab, sigma, src[0],
                      src[1], src[2], src[3], src[4], src[5], src[6], keep_d ? 1 : 0);
+  return hipGetLastError();
+}
+
+hipError_t launch_ny_unscramble(int64_t n, double *x, double *y, hipStream_t s) {
+  hipLaunchKernelGGL(k_ny_unscramble, grid_for(n), dim3(256), 0, s, n, x, y);
   return hipGetLastError();
 }
 

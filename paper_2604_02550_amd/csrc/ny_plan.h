@@ -26,8 +26,13 @@
 // indices, of r^2 x r^2 x r^2 products of spatial blocks.  The planner
 // enumerates the spin assignments, keeps the canonical output blocks the
 // final combination needs (and those the first stages must produce for
-// them), and emits permutations of source blocks into GEMM operand layout and
-// the GEMM list.
+// them), counts the two equal opposite-spin terms of a summed antisymmetric
+// pair once with weight 2, and computes two output blocks that share their
+// operands crosswise (x = A1 B1 + A2 B2, y = A1 B2 + A2 B1) from the products
+// of the sums and of the differences.  It emits the operand builds (source
+// blocks permuted into GEMM operand layout, intermediates converted from
+// their FP64 staging, and the sums and differences), the product list and the
+// unscrambling passes: 18 block products per map.
 #pragma once
 #include <cstdint>
 #include <cstring>
@@ -94,23 +99,6 @@ inline int block_of(const char *letters, const std::map<char, int> &spin) {
   return b;
 }
 
-// One permutation of a source block into GEMM operand layout:
-// buf[(x0 r + x1) ld + x2 r + x3] = src_block[sum_t x_t st[t]].
-struct PermOp {
-  int src, block;  // source tensor, canonical block
-  int layout;      // index into Plan::layouts
-  int buf;         // operand buffer id
-};
-
-struct GemmOp {
-  int a_buf, b_buf;   // operand buffer ids
-  int out, block;     // output tensor and canonical block
-  int stage;
-  int accumulate;     // 0 for the first term of an output block
-  int term;           // term index within the output block
-  double alpha;       // 2 where the term stands for itself and its pair-exchanged twin
-};
-
 // K letters that are the two indices of one pair (positions 0,1 or 2,3) of a
 // source tensor: the source is antisymmetric under their exchange.
 inline bool source_pair(const char *nat, const char *k) {
@@ -118,14 +106,44 @@ inline bool source_pair(const char *nat, const char *k) {
   return a >= 0 && b >= 0 && (a >> 1) == (b >> 1);
 }
 
+// One GEMM operand built in operand layout: T1[b1] + c2 T2[b2] (t2 < 0: T1[b1]
+// alone), canonical blocks of one tensor kind.  Sources are permuted from
+// their natural arrays (layout >= 0); intermediates are read from their FP64
+// staging buffers in the same layout (layout < 0).
+struct OperandBuild {
+  int t1, b1, t2, b2;
+  double c2;
+  int layout;
+  int phase;   // 0: read by the first-stage products, 1: by the second stages
+  int buf;     // operand buffer id
+};
+
+struct Product {
+  int a_buf, b_buf;  // operand buffer ids
+  int out, block;    // output tensor and canonical block
+  int stage, phase;
+  int accumulate;    // 0 for the first term of an output block
+  int term;          // term index within the output block
+  double alpha;      // 2 where the term stands for itself and its pair-exchanged twin
+};
+
+// Two output blocks x, y with x = A1 B1 + A2 B2 and y = A1 B2 + A2 B1 are
+// computed as P = (A1 + A2)(B1 + B2) into x and Q = (A1 - A2)(B1 - B2) into y,
+// then (x, y) <- ((x + y) / 2, (x - y) / 2): two products instead of four.
+struct Unscramble {
+  int out, bx, by;
+  int phase;
+};
+
 struct Plan {
-  std::vector<std::string> layouts;      // source letters + row/K letters, per PermOp
+  std::vector<std::string> layouts;      // source letters + row/K letters
   std::vector<int64_t> layout_strides;   // 4 per layout, in units of natural strides (0..3 = r^3..1)
-  std::vector<PermOp> perms;
-  std::vector<GemmOp> gemms;
-  int num_bufs = 0;                      // operand buffers (permuted sources + intermediates)
-  std::map<std::pair<int, int>, int> inter_buf;   // (tensor, canonical block) -> buffer
-  std::map<std::pair<int, int>, int> product_nat; // (product tensor, canonical block) -> natural array id
+  std::vector<OperandBuild> operands;
+  std::vector<Product> products;
+  std::vector<Unscramble> unscrambles;
+  int num_bufs = 0;                                // operand buffers
+  std::map<std::pair<int, int>, int> staging;      // (intermediate, canonical block) -> FP64 staging buffer
+  std::map<std::pair<int, int>, int> product_nat;  // (product tensor, canonical block) -> natural array id
   int num_nat = 0;
 };
 
@@ -142,10 +160,10 @@ inline Plan build_plan() {
   };
   std::vector<std::map<int, std::vector<std::pair<int, int>>>> terms(ns);
   std::vector<std::map<int, std::vector<double>>> alphas(ns);
-  std::vector<bool> twin_pairs(ns);
   for (int s = 0; s < ns; ++s) {
     const Stage &S = st[s];
-    twin_pairs[s] = is_source(S.a) && is_source(S.b) && source_pair(S.la, S.ka) && source_pair(S.lb, S.kb);
+    const bool twin_pairs =
+        is_source(S.a) && is_source(S.b) && source_pair(S.la, S.ka) && source_pair(S.lb, S.kb);
     std::string letters;
     for (const char *q : {S.la, S.lb})
       for (int t = 0; t < 4; ++t)
@@ -161,11 +179,11 @@ inline Plan build_plan() {
       // (source) operands, the terms with its two spins exchanged are equal:
       // keep the one with the first K index alpha, counted twice.
       double alpha = 1.0;
-      if (twin_pairs[s] && spin.at(S.ka[0]) != spin.at(S.ka[1])) {
+      if (twin_pairs && spin.at(S.ka[0]) != spin.at(S.ka[1])) {
         if (spin.at(S.ka[0]) == 1) continue;
         alpha = 2.0;
       }
-      terms[s][bo].push_back({ba, bb});
+      terms[s][bo].push_back({canon(ba), canon(bb)});
       alphas[s][bo].push_back(alpha);
     }
     for (auto &kv : terms[s]) produced.insert({S.out, kv.first});
@@ -183,14 +201,21 @@ inline Plan build_plan() {
     for (auto &kv : terms[s]) {
       if (!needed.count({S.out, kv.first})) continue;
       for (auto &ab : kv.second) {
-        if (!is_source(S.a)) needed.insert({S.a, canon(ab.first)});
-        if (!is_source(S.b)) needed.insert({S.b, canon(ab.second)});
+        if (!is_source(S.a)) needed.insert({S.a, ab.first});
+        if (!is_source(S.b)) needed.insert({S.b, ab.second});
       }
     }
   }
-  // buffers and operations
-  std::map<std::tuple<int, int, std::string>, int> perm_buf;
-  auto layout_id = [&](int src, const char *nat, const char *rows, const char *k) {
+  // output storage
+  for (int s = 0; s < ns; ++s)
+    for (auto &kv : terms[s]) {
+      if (!needed.count({st[s].out, kv.first})) continue;
+      if (is_product(st[s].out)) P.product_nat[{st[s].out, kv.first}] = P.num_nat++;
+      else P.staging[{st[s].out, kv.first}] = (int)P.staging.size();
+    }
+  // operands, shared by key
+  std::map<std::tuple<std::string, int, int, int, int, double>, int> op_buf;
+  auto layout_id = [&](const char *nat, const char *rows, const char *k) {
     std::string key = std::string(nat) + ":" + rows + k;
     for (size_t q = 0; q < P.layouts.size(); ++q)
       if (P.layouts[q] == key) return (int)q;
@@ -199,44 +224,55 @@ inline Plan build_plan() {
       const char c = t < 2 ? rows[t] : k[t - 2];
       P.layout_strides.push_back(letter_pos(nat, c));
     }
-    (void)src;
     return (int)P.layouts.size() - 1;
   };
-  auto operand = [&](int tensor, int block, const char *nat, const char *rows, const char *k) {
-    const int cb = canon(block);
-    if (!is_source(tensor)) return P.inter_buf.at({tensor, cb});
-    const int lay = layout_id(tensor, nat, rows, k);
-    auto key = std::make_tuple(tensor, cb, P.layouts[lay]);
-    auto it = perm_buf.find(key);
-    if (it != perm_buf.end()) return it->second;
+  auto operand = [&](int s, int side, int t, int b1, int b2, double c2) {
+    const Stage &S = st[s];
+    const int lay = is_source(t) ? (side ? layout_id(S.lb, S.rb, S.kb) : layout_id(S.la, S.ra, S.ka)) : -1;
+    const std::string lk = lay >= 0 ? P.layouts[lay] : std::string("staging");
+    auto key = std::make_tuple(lk, t, b1, b2 < 0 ? -1 : t, b2, c2);
+    auto it = op_buf.find(key);
+    if (it != op_buf.end()) return it->second;
     const int id = P.num_bufs++;
-    perm_buf[key] = id;
-    P.perms.push_back({tensor, cb, lay, id});
+    op_buf[key] = id;
+    P.operands.push_back({t, b1, b2 < 0 ? -1 : t, b2, c2, lay, s >= ns / 2 ? 1 : 0, id});
     return id;
   };
   for (int s = 0; s < ns; ++s) {
     const Stage &S = st[s];
-    for (auto &kv : terms[s]) {
-      const int bo = kv.first;
-      if (!needed.count({S.out, bo})) continue;
-      if (is_product(S.out)) {
-        P.product_nat[{S.out, bo}] = P.num_nat++;
-      } else {
-        P.inter_buf[{S.out, bo}] = P.num_bufs++;
+    const int phase = s >= ns / 2 ? 1 : 0;
+    std::set<int> done;
+    // crosswise pairs of output blocks
+    for (auto &x : terms[s]) {
+      if (!needed.count({S.out, x.first}) || done.count(x.first) || x.second.size() != 2) continue;
+      const auto &tx = x.second;
+      if (alphas[s][x.first][0] != 1.0 || alphas[s][x.first][1] != 1.0) continue;
+      const int a1 = tx[0].first, b1 = tx[0].second, a2 = tx[1].first, b2 = tx[1].second;
+      if (a1 == a2 || b1 == b2) continue;
+      for (auto &y : terms[s]) {
+        if (y.first == x.first || !needed.count({S.out, y.first}) || done.count(y.first) || y.second.size() != 2)
+          continue;
+        if (alphas[s][y.first][0] != 1.0 || alphas[s][y.first][1] != 1.0) continue;
+        std::set<std::pair<int, int>> want = {{a1, b2}, {a2, b1}}, have(y.second.begin(), y.second.end());
+        if (want != have) continue;
+        const int ap = operand(s, 0, S.a, a1, a2, 1.0), bp = operand(s, 1, S.b, b1, b2, 1.0);
+        const int am = operand(s, 0, S.a, a1, a2, -1.0), bm = operand(s, 1, S.b, b1, b2, -1.0);
+        P.products.push_back({ap, bp, S.out, x.first, s, phase, 0, 0, 1.0});
+        P.products.push_back({am, bm, S.out, y.first, s, phase, 0, 0, 1.0});
+        P.unscrambles.push_back({S.out, x.first, y.first, phase});
+        done.insert(x.first);
+        done.insert(y.first);
+        break;
       }
+    }
+    for (auto &x : terms[s]) {
+      if (!needed.count({S.out, x.first}) || done.count(x.first)) continue;
       int term = 0;
-      const std::vector<double> &al = alphas[s][bo];
-      for (auto &ab : kv.second) {
-        GemmOp g{};
-        g.alpha = al[term];
-        g.a_buf = operand(S.a, ab.first, S.la, S.ra, S.ka);
-        g.b_buf = operand(S.b, ab.second, S.lb, S.rb, S.kb);
-        g.out = S.out;
-        g.block = bo;
-        g.stage = s;
-        g.accumulate = term > 0;
-        g.term = term++;
-        P.gemms.push_back(g);
+      for (size_t q = 0; q < x.second.size(); ++q) {
+        const int ab = operand(s, 0, S.a, x.second[q].first, -1, 0.0);
+        const int bb = operand(s, 1, S.b, x.second[q].second, -1, 0.0);
+        P.products.push_back({ab, bb, S.out, x.first, s, phase, term > 0, term, alphas[s][x.first][q]});
+        ++term;
       }
     }
   }
