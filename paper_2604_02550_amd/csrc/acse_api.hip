@@ -22,6 +22,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <exception>
 #include <string>
 #include <initializer_list>
 #include <map>
@@ -475,10 +476,24 @@ acse_status ensure_ny_ws(acse_ctx c) {
   return ACSE_OK;
 }
 
+acse_status ny_share_run(acse_ctx c, const acse_problem *p, GemmPrec prec, const double *Xaa,
+                         const double *Xab, double *Saa, double *Sab);
+
 // The NY share of F(X): S_aa -= C_aa, S_ab -= C_ab (C = B - B(k<->l), B the
-// 3-cumulant's share of the 3-RDM contraction), on the plan of ny_plan.h.
+// 3-cumulant's share of the 3-RDM contraction), on the plan of ny_plan.h.  No
+// C++ exception (an allocation of the plan's containers, a plan lookup)
+// leaves through the C interface.
 acse_status ny_share(acse_ctx c, const acse_problem *p, GemmPrec prec, const double *Xaa, const double *Xab,
                      double *Saa, double *Sab) {
+  try {
+    return ny_share_run(c, p, prec, Xaa, Xab, Saa, Sab);
+  } catch (const std::exception &e) {
+    return fail(c, ACSE_ERR_NOMEM, std::string("Nakatsuji-Yasuda share: ") + e.what());
+  }
+}
+
+acse_status ny_share_run(acse_ctx c, const acse_problem *p, GemmPrec prec, const double *Xaa,
+                         const double *Xab, double *Saa, double *Sab) {
   const int r = p->r;
   hipStream_t s = c->stream;
   StageTimer t6(c, 6);

@@ -25,7 +25,8 @@ test_oracle_ny.py).
   residual, sigma entries other than +1 / -1.
 * Edges: r = 2 and 3; the step with the active-active mask on the
   general-size kernels; the update map on an anti-Hermitian direction that is
-  not a residual.
+  not a residual; the backtracking control (rejected trials) with the input
+  symmetry check on.
 """
 import json
 import os
@@ -331,3 +332,32 @@ def test_ny_r50_residual_vs_stored_oracle(acse, precision, tol):
         assert abs(n2 - g["norm2"]) <= tol * g["norm2"]
     finally:
         ctx.close()
+
+
+def test_ny_backtracking_solve_and_input_check(acse):
+    """The backtracking control with the NY 3-RDM (a step size that overshoots
+    first) against the oracle's iteration, with the input-symmetry check on."""
+    r, N = 6, 4
+    p = gen.problem(r, N, 12, seed=1)
+    _, d2 = rdm.blocks_to_spin_orbital(np.eye(r), p["d2aa"], p["d2ab"])
+    p["gamma"] = rdm.contract_to_1rdm(d2, N)[:r, :r]
+    sig = np.array([1, -1, 1, -1, -1, 1], dtype=float)
+    print(f"[ny] backtracking solve r={r}", flush=True)
+    o = sv.euler(p["h"], p["V"], N, p["gamma"], p["d2aa"], p["d2ab"], eps=0.1, de_tol=0.0, max_iter=3,
+                 control=sv.BACKTRACK, max_halvings=12, sigma=sig)
+    assert any(not t[4] for t in o["trials"])  # at least one rejected trial
+    ctx = acse.Context(r_max=r)
+    try:
+        g = ctx.solve(p["h"], p["V"], p["gamma"], p["d2aa"], p["d2ab"], N // 2, eps=0.1, de_tol=0.0, max_iter=3,
+                      control="backtrack", max_halvings=12, flags=acse.FLAG_CHECK_INPUTS,
+                      sigma=[int(x) for x in sig])
+    finally:
+        ctx.close()
+    assert g["stop"] == ("max_iter", "converged", "energy_rose", "norm_rose")[o["stop"]]
+    assert len(g["trials"]) == len(o["trials"])
+    for (ge, gE, gf, gn, ga), (oe, oE, of, on, oa) in zip(g["trials"], o["trials"]):
+        assert gn == on and ga == oa and ge == oe
+        assert abs(gE - oE) <= 1e-10 * max(1.0, abs(oE))
+        assert abs(gf - of) <= 1e-10 * of
+    for key in ("d2aa", "d2ab"):
+        assert np.abs(g[key].cpu().numpy() - o[key]).max() <= 1e-10 * np.abs(o[key]).max(), key
