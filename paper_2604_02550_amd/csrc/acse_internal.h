@@ -35,7 +35,7 @@ struct GemmProb {
   int accumulate;     // 1: C += alpha * AB^T
 };
 
-constexpr int kMaxGemmProbs = 6;
+constexpr int kMaxGemmProbs = 10;  // the by-value batch stays within the 4 KiB kernel-argument limit (2.3 KiB)
 constexpr int kGemmXcds = 8;  // XCDs of the device, each with its own L2
 // Logical tile order of a grouped launch: segment s (in order) covers logical
 // tiles [seg_start[s], seg_start[s+1]) = tiles seg_local[s]... of problem
