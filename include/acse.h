@@ -101,7 +101,8 @@ typedef struct {
                              option of the method section); the norm is taken first. */
   int32_t tile;           /* GEMM tile configuration, -1 = autotuned default */
   int32_t flags;          /* bitwise OR of ACSE_FLAG_* (0 = none) */
-  int32_t reconstruction; /* acse_reconstruction of the 3-RDM (0 = Valdemoro) */
+  int32_t reconstruction; /* acse_reconstruction of the 3-RDM (0 = Valdemoro); other values
+                             are an ACSE_ERR_ARG */
   const int8_t *ny_sigma; /* HOST [r] or NULL, ACSE_RECON_NY only: +1 for an orbital occupied
                              in the Hartree-Fock reference, -1 for an unoccupied one;
                              NULL = orbitals 0 .. n_alpha-1 occupied.  Other values are an
