@@ -251,11 +251,17 @@ def bench_ny(acse, ctx, prob, work, pristine, torch, stream, steps, warmup, eps,
     E1, n2 = ctx.step_raw(prob, eps, opts)
     restore()
     ny_ms = prof["ny_share"][0] / steps
+    gemm_ms = prof["ny_gemm"][0] / steps
     flops = 2 * NY_BLOCK_GEMMS * 2.0 * r ** 6
+    achieved = flops / (gemm_ms * 1e-3) / 1e12
     return dict(ms_per_step=ms, steps_per_s=1e3 / ms, over_valdemoro_step=ms / v_step_ms,
                 stage_ms_per_step={k: v[0] / steps for k, v in prof.items()},
                 ny_share_ms_per_step=ny_ms, ny_block_gemm_flops_per_step=flops,
                 ny_share_tflops=flops / (ny_ms * 1e-3) / 1e12,
+                roofline={"bound": "mfma", "achieved": achieved, "peak": PEAK_TFLOPS[mode], "unit": "TFLOP/s",
+                          "frac": achieved / PEAK_TFLOPS[mode],
+                          "kernel": "gemm_nt_kernel on the NY block products (18 of r^2 x r^2 x r^2 per map, "
+                                    "HIP-event time of their launches)"},
                 energy_identity_rel=abs((E1 - E0) + eps * n2) / (eps * n2))
 
 

@@ -303,12 +303,14 @@ acse_status acse_energy_vjp(acse_ctx ctx, const acse_problem *prob, double Ebar,
  *   3  grouped pair-index GEMM (the six O(r^6) contractions of one map)
  *   4  assembly, (ij)<->(kl) exchange and the FP64 norm
  *   5  step tail: axpy, trace restoration, 1-RDM contraction, energy
- *   6  Nakatsuji-Yasuda share (cumulant blocks, operand layouts, its GEMMs
- *      and the combination into the map; ACSE_RECON_NY only)
+ *   6  Nakatsuji-Yasuda share, whole (cumulant blocks, operand builds, its
+ *      block GEMMs, unscrambling and the combination into the map;
+ *      ACSE_RECON_NY only)
+ *   7  the block GEMMs of the Nakatsuji-Yasuda share alone (inside stage 6)
  * acse_profile_enable(ctx, 1) clears the totals and starts recording;
  * acse_profile_read synchronises the stream and returns the totals (ms and
  * number of timed intervals per stage) since the last enable. */
-#define ACSE_NUM_STAGES 7
+#define ACSE_NUM_STAGES 8
 typedef struct {
   double ms[ACSE_NUM_STAGES];
   int64_t count[ACSE_NUM_STAGES];

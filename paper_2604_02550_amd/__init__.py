@@ -35,8 +35,8 @@ EXPORTS = ("acse_create", "acse_destroy", "acse_set_stream", "acse_residual", "a
            "acse_residual_vjp", "acse_energy_vjp", "acse_residual_batched",
            "acse_autotune_batched", "acse_solve")
 NUM_TILE_CONFIGS = 3
-NUM_STAGES = 7
-STAGES = ("rdm_operands", "fold", "transforms", "gemm", "assembly", "step_tail", "ny_share")
+NUM_STAGES = 8
+STAGES = ("rdm_operands", "fold", "transforms", "gemm", "assembly", "step_tail", "ny_share", "ny_gemm")
 
 
 class Problem(ctypes.Structure):

@@ -140,8 +140,10 @@ struct StageTimer {
       c->recs.push_back({stage, a, b});
     }
   }
-  ~StageTimer() {
+  ~StageTimer() { stop(); }
+  void stop() {
     if (c->profiling && b) (void)hipEventRecord(b, c->stream);
+    b = nullptr;
   }
   hipEvent_t take() {
     if (!c->pool.empty()) { hipEvent_t e = c->pool.back(); c->pool.pop_back(); return e; }
@@ -566,7 +568,9 @@ acse_status ny_share_run(acse_ctx c, const acse_problem *p, GemmPrec prec, const
       HIP_TRY(c, launch_permute4(prec, a, opref(o.buf), s));
     }
     // products: the t-th terms of all output blocks of the phase go out
-    // together (distinct outputs), up to kMaxGemmProbs a launch
+    // together (distinct outputs), up to kMaxGemmProbs a launch (timed as
+    // their own stage)
+    StageTimer t7(c, 7);
     for (int term = 0;; ++term) {
       std::vector<const ny::Product *> round;
       for (const ny::Product &g : P.products)
@@ -592,6 +596,7 @@ acse_status ny_share_run(acse_ctx c, const acse_problem *p, GemmPrec prec, const
         HIP_TRY(c, gemm_launch(prec, cfg, batch, s));
       }
     }
+    t7.stop();
     for (const ny::Unscramble &u : P.unscrambles) {
       if (u.phase != phase) continue;
       if (ny::is_product(u.out)) {
