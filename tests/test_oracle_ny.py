@@ -4,7 +4,9 @@ part), CPU only.
 * Second order: for a determinant with a doubles admixture of amplitude t, the
   exact 3-cumulant (Fock-space 3-RDM minus the Valdemoro terms) is O(t^2) and
   the NY formula, evaluated on the exact 2-cumulant with sigma from the
-  determinant's occupations, matches it up to O(t^3).  This fixes the 1/6, the
+  determinant's occupations, matches it up to O(t^3); for a prefix of
+  occupied orbitals and for a scattered set (sigma follows the orbital, not
+  its position).  This fixes the 1/6, the
   36-term antisymmetriser and the normalisation of 2Delta; a factor 2 or a
   sign flip leaves an O(t^2) error and fails.
 * Invariants of the NY 3-cumulant: antisymmetric within the upper and within
@@ -39,15 +41,15 @@ def _doubles_state(fock, occ, amp, t):
     return psi / np.linalg.norm(psi)
 
 
-@pytest.fixture(scope="module")
-def second_order():
+@pytest.fixture(scope="module", params=[(0, 1), (1, 3)], ids=["occ01", "occ13"])
+def second_order(request):
     n = 8
     fock = fm.Fock(n)
-    occ = [0, 1, 4, 5]
+    occ = [q for o in request.param for q in (o, o + 4)]  # both spins of the occupied spatial orbitals
     amp = np.random.default_rng(3).standard_normal((n, n, n, n))
     sigma = np.array([1.0 if p in occ else -1.0 for p in range(n)])
     out = []
-    for t in (0.05, 0.025, 0.0125):
+    for t in (0.025, 0.0125, 0.00625):
         psi = _doubles_state(fock, occ, amp, t)
         d1 = fock.rdm1(psi)
         d2 = 0.5 * fock.rdm2(psi)
