@@ -2,8 +2,8 @@
 part) against the oracle (tier B with the NY share, pinned in
 test_oracle_ny.py).
 
-* Residual at r = 4, 9, 16 (r^2 = 16 .. 256: one to two GEMM tiles with ragged
-  edges) with the default reference occupations and with sigma patterns that
+* Residual at r = 4, 9, 16, 24 (r^2 = 16 .. 576: one to five GEMM tiles with
+  ragged edges) with the default reference occupations and with sigma patterns that
   are not a prefix; FP64 bar 1e-10 of the largest element, on the residual
   and, separately, on the NY share alone (NY residual minus Valdemoro
   residual, both from the same side), so a wrong share cannot hide below the
@@ -68,7 +68,7 @@ def sigma_of(p, pattern):
 
 
 CASES = [(4, 4, 0, "prefix"), (4, 4, 1, (-1, 1, -1, 1)), (9, 8, 2, "prefix"),
-         (9, 8, 3, (1, -1, 1, 1, -1, 1, -1, -1, 1)), (16, 10, 4, "prefix")]
+         (9, 8, 3, (1, -1, 1, 1, -1, 1, -1, -1, 1)), (16, 10, 4, "prefix"), (24, 14, 6, "prefix")]
 
 
 @pytest.mark.parametrize("r,N,seed,pattern", CASES)
