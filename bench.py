@@ -250,11 +250,25 @@ def bench_ny(acse, ctx, prob, work, pristine, torch, stream, steps, warmup, eps,
     E0 = ctx.energy_raw(prob)
     E1, n2 = ctx.step_raw(prob, eps, opts)
     restore()
+    # residual-only rate with the NY 3-RDM (the oracle is timed on the same call)
+    R = [torch.empty((r, r, r, r), dtype=torch.float64, device="cuda") for _ in range(2)]
+    ctx.residual_raw(prob, opts, R[0], R[1], want_norm=False)
+    torch.cuda.synchronize()
+    s2 = torch.cuda.Event(enable_timing=True)
+    e2 = torch.cuda.Event(enable_timing=True)
+    s2.record(stream)
+    for _ in range(steps):
+        ctx.residual_raw(prob, opts, R[0], R[1], want_norm=False)
+    e2.record(stream)
+    torch.cuda.synchronize()
+    res_ms = s2.elapsed_time(e2) / steps
+    del R
     ny_ms = prof["ny_share"][0] / steps
     gemm_ms = prof["ny_gemm"][0] / steps
     flops = 2 * NY_BLOCK_GEMMS * 2.0 * r ** 6
     achieved = flops / (gemm_ms * 1e-3) / 1e12
     return dict(ms_per_step=ms, steps_per_s=1e3 / ms, over_valdemoro_step=ms / v_step_ms,
+                residual_ms=res_ms, residual_evals_per_s=1e3 / res_ms,
                 stage_ms_per_step={k: v[0] / steps for k, v in prof.items()},
                 ny_share_ms_per_step=ny_ms, ny_block_gemm_flops_per_step=flops,
                 ny_share_tflops=flops / (ny_ms * 1e-3) / 1e12,
@@ -440,6 +454,15 @@ def main():
                                 "kind": "oracle",
                                 "sample": f"one FP64 oracle residual at r={r}, N={N} (spin-orbital "
                                           f"factorised form, {dt:.1f} s)"}
+        if args.ny_steps > 0 and "fp64" in line.get("nakatsuji_yasuda", {}):
+            sigma = np.where(np.arange(r) < N // 2, 1.0, -1.0)
+            t0 = time.perf_counter()
+            ost.residual(p["h"], p["V"], p["N"], p["gamma"], p["d2aa"], p["d2ab"], sigma=sigma)
+            dt = time.perf_counter() - t0
+            line["nakatsuji_yasuda"]["fp64"]["cpu_baseline"] = {
+                "value": 1.0 / dt, "unit": "residual evals/s", "cores": threads, "kind": "oracle",
+                "sample": f"one FP64 oracle residual with the NY 3-RDM at r={r}, N={N} (spin-orbital "
+                          f"factorised form, {dt:.1f} s)"}
     print(json.dumps(line), flush=True)
 
 
