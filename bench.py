@@ -213,15 +213,19 @@ def bench_solve(acse, ctx, prob, work, pristine, torch, controls, iters, eps, st
     return res
 
 
-NY_BLOCK_GEMMS = 18  # spatial-block products of the NY share per map (the plan of ny_plan.h)
+def ny_map_flops(r):
+    """Flops the NY share's block products execute per map (the plan of
+    ny_plan.h): 17 products of r^2 x r^2 x r^2 and one whose summed pair is
+    packed to r(r-1)/2 columns."""
+    return 2.0 * r ** 6 * (17 + (r * (r - 1) / 2) / r ** 2)
 
 
 def bench_ny(acse, ctx, prob, work, pristine, torch, stream, steps, warmup, eps, v_step_ms, mode="fp64"):
     """One acse_step with the Nakatsuji-Yasuda 3-RDM (Eq. (8)) on the same
-    workload, block products in `mode`: ms per step, the stage split with the
-    NY share's own stage, and the share's rate in issued block-GEMM flops (28
-    products of 2 r^6 per map) per second of its stage (permutations,
-    cumulant blocks and the combination included).  The check is
+    workload, block products in `mode`: ms per step, the residual-only time,
+    the stage split with the NY share's own stages, the share's rate in
+    executed block-GEMM flops (ny_map_flops per map) per second of its whole
+    stage, and the roofline of the block GEMM launches alone.  The check is
     E1 - E0 = -eps ||R||^2."""
     r = prob.r
     opts = acse.Context.options(mode, sigma=True)
@@ -265,7 +269,7 @@ def bench_ny(acse, ctx, prob, work, pristine, torch, stream, steps, warmup, eps,
     del R
     ny_ms = prof["ny_share"][0] / steps
     gemm_ms = prof["ny_gemm"][0] / steps
-    flops = 2 * NY_BLOCK_GEMMS * 2.0 * r ** 6
+    flops = 2 * ny_map_flops(r)
     achieved = flops / (gemm_ms * 1e-3) / 1e12
     return dict(ms_per_step=ms, steps_per_s=1e3 / ms, over_valdemoro_step=ms / v_step_ms,
                 residual_ms=res_ms, residual_evals_per_s=1e3 / res_ms,
@@ -274,7 +278,7 @@ def bench_ny(acse, ctx, prob, work, pristine, torch, stream, steps, warmup, eps,
                 ny_share_tflops=flops / (ny_ms * 1e-3) / 1e12,
                 roofline={"bound": "mfma", "achieved": achieved, "peak": PEAK_TFLOPS[mode], "unit": "TFLOP/s",
                           "frac": achieved / PEAK_TFLOPS[mode],
-                          "kernel": "gemm_nt_kernel on the NY block products (18 of r^2 x r^2 x r^2 per map, "
+                          "kernel": "gemm_nt_kernel on the NY block products (18 per map, one with its summed pair packed; "
                                     "HIP-event time of their launches)"},
                 energy_identity_rel=abs((E1 - E0) + eps * n2) / (eps * n2))
 

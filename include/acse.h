@@ -115,9 +115,9 @@ typedef struct {
  *                  sigma-weighted, antisymmetrised product of two 2-cumulants
  *                  of Eq. (8) (App. D, NY part), never formed.  Both maps of
  *                  a step use it.  Its share runs as 18 spatial-block GEMMs
- *                  of r^2 x r^2 x r^2 per map (a spin-orbital contraction split
- *                  over the spins of its internal indices) in the call's
- *                  precision; its combination into the map is FP64.  The
+ *                  of r^2 x r^2 x r^2 per map (one with K packed to r(r-1)/2;
+ *                  a spin-orbital contraction split over the spins of its
+ *                  internal indices) in the call's precision; its combination into the map is FP64.  The
  *                  first NY call allocates its workspace for r_max (about
  *                  (19 r^4 + 44 r^4-sized operand buffers) x 8 bytes: 3.3 GB at
  *                  r_max = 50; ACSE_ERR_NOMEM if that fails).  The adjoint

@@ -535,6 +535,8 @@ acse_status ny_share_run(acse_ctx c, const acse_problem *p, GemmPrec prec, const
   const ny::Stage *stg = ny::stages(&ns);
   const int cfg = map_cfg(c, prec, r, -1);
   const int kp = gemm_kp(prec, (int)r2, (int)ld);
+  const int64_t ld_lt = ld_pair_lt(r);
+  const int kp_lt = gemm_kp(prec, npair_lt(r), (int)ld_lt);
   for (int phase = 0; phase < 2; ++phase) {
     // operands of this phase: source blocks permuted into operand layout, or
     // intermediates converted from their FP64 staging; sums and differences
@@ -543,6 +545,21 @@ acse_status ny_share_run(acse_ctx c, const acse_problem *p, GemmPrec prec, const
       if (o.phase != phase) continue;
       const bool src_op = ny::is_source(o.t1);
       if (keep_d && src_op && o.t1 != ny::T_X) continue;
+      if (o.packed) {  // K over the pairs k0 < k1 of one source block
+        if (!src_op || o.t2 >= 0) return fail(c, ACSE_ERR_UNSUPPORTED, "NY plan: unsupported packed operand");
+        PairPackArgs pa{};
+        pa.r = r;
+        pa.rows_mode = 0;
+        pa.k_le = 0;
+        pa.ld = ld_lt;
+        pa.nterms = 1;
+        pa.src[0] = src[o.t1][slot(o.b1)];
+        for (int t = 0; t < 4; ++t) pa.st[0][t] = nst[P.layout_strides[4 * o.layout + t]];
+        pa.c[0] = 1.0;
+        pa.offdiag[0] = 0;
+        HIP_TRY(c, launch_pack_pairs(prec, pa, opref(o.buf), s));
+        continue;
+      }
       PermArgs a{};
       a.r = r;
       a.rows = rows;
@@ -589,9 +606,11 @@ acse_status ny_share_run(acse_ctx c, const acse_problem *p, GemmPrec prec, const
           G.A = ra.hi; G.A2 = ra.lo; G.B = rb.hi; G.B2 = rb.lo;
           G.C = ny::is_product(g.out) ? q.prod[P.product_nat.at({g.out, g.block})] : stage_of(g.out, g.block);
           G.alpha = g.alpha;
-          G.M = (int)r2; G.N = (int)r2; G.Kp = kp; G.ld = (int)ld; G.rdiv = r;
+          G.M = (int)r2; G.N = (int)r2; G.rdiv = r;
+          G.Kp = g.packed ? kp_lt : kp;
+          G.ld = g.packed ? (int)ld_lt : (int)ld;
           G.sm1 = os[0]; G.sm0 = os[1]; G.sn1 = os[2]; G.sn0 = os[3];
-          G.ksplit = 1; G.kchunk = kp; G.accumulate = g.accumulate;
+          G.ksplit = 1; G.kchunk = G.Kp; G.accumulate = g.accumulate;
         }
         HIP_TRY(c, gemm_launch(prec, cfg, batch, s));
       }

@@ -116,6 +116,7 @@ struct OperandBuild {
   int layout;
   int phase;   // 0: read by the first-stage products, 1: by the second stages
   int buf;     // operand buffer id
+  int packed;  // K over the pairs k0 < k1 only (rows all r^2): see Product::packed
 };
 
 struct Product {
@@ -125,6 +126,8 @@ struct Product {
   int accumulate;    // 0 for the first term of an output block
   int term;          // term index within the output block
   double alpha;      // 2 where the term stands for itself and its pair-exchanged twin
+  int packed;        // the summed pair is antisymmetric within both operand blocks (equal
+                     // spins): K runs over k0 < k1 only, alpha doubled
 };
 
 // Two output blocks x, y with x = A1 B1 + A2 B2 and y = A1 B2 + A2 B1 are
@@ -160,6 +163,7 @@ inline Plan build_plan() {
   };
   std::vector<std::map<int, std::vector<std::pair<int, int>>>> terms(ns);
   std::vector<std::map<int, std::vector<double>>> alphas(ns);
+  std::vector<std::map<int, std::vector<int>>> packs(ns);
   for (int s = 0; s < ns; ++s) {
     const Stage &S = st[s];
     const bool twin_pairs =
@@ -178,13 +182,20 @@ inline Plan build_plan() {
       // Where the summed index pair is one antisymmetric pair of both
       // (source) operands, the terms with its two spins exchanged are equal:
       // keep the one with the first K index alpha, counted twice.
+      // With equal spins the pair is antisymmetric within both blocks: the
+      // sum over k0 != k1 is twice the sum over k0 < k1.
       double alpha = 1.0;
+      int packed = 0;
       if (twin_pairs && spin.at(S.ka[0]) != spin.at(S.ka[1])) {
         if (spin.at(S.ka[0]) == 1) continue;
         alpha = 2.0;
+      } else if (twin_pairs) {
+        alpha = 2.0;
+        packed = 1;
       }
       terms[s][bo].push_back({canon(ba), canon(bb)});
       alphas[s][bo].push_back(alpha);
+      packs[s][bo].push_back(packed);
     }
     for (auto &kv : terms[s]) produced.insert({S.out, kv.first});
   }
@@ -214,7 +225,7 @@ inline Plan build_plan() {
       else P.staging[{st[s].out, kv.first}] = (int)P.staging.size();
     }
   // operands, shared by key
-  std::map<std::tuple<std::string, int, int, int, int, double>, int> op_buf;
+  std::map<std::tuple<std::string, int, int, int, int, double, int>, int> op_buf;
   auto layout_id = [&](const char *nat, const char *rows, const char *k) {
     std::string key = std::string(nat) + ":" + rows + k;
     for (size_t q = 0; q < P.layouts.size(); ++q)
@@ -226,16 +237,16 @@ inline Plan build_plan() {
     }
     return (int)P.layouts.size() - 1;
   };
-  auto operand = [&](int s, int side, int t, int b1, int b2, double c2) {
+  auto operand = [&](int s, int side, int t, int b1, int b2, double c2, int packed) {
     const Stage &S = st[s];
     const int lay = is_source(t) ? (side ? layout_id(S.lb, S.rb, S.kb) : layout_id(S.la, S.ra, S.ka)) : -1;
     const std::string lk = lay >= 0 ? P.layouts[lay] : std::string("staging");
-    auto key = std::make_tuple(lk, t, b1, b2 < 0 ? -1 : t, b2, c2);
+    auto key = std::make_tuple(lk, t, b1, b2 < 0 ? -1 : t, b2, c2, packed);
     auto it = op_buf.find(key);
     if (it != op_buf.end()) return it->second;
     const int id = P.num_bufs++;
     op_buf[key] = id;
-    P.operands.push_back({t, b1, b2 < 0 ? -1 : t, b2, c2, lay, s >= ns / 2 ? 1 : 0, id});
+    P.operands.push_back({t, b1, b2 < 0 ? -1 : t, b2, c2, lay, s >= ns / 2 ? 1 : 0, id, packed});
     return id;
   };
   for (int s = 0; s < ns; ++s) {
@@ -246,19 +257,23 @@ inline Plan build_plan() {
     for (auto &x : terms[s]) {
       if (!needed.count({S.out, x.first}) || done.count(x.first) || x.second.size() != 2) continue;
       const auto &tx = x.second;
-      if (alphas[s][x.first][0] != 1.0 || alphas[s][x.first][1] != 1.0) continue;
+      if (alphas[s][x.first][0] != 1.0 || alphas[s][x.first][1] != 1.0 || packs[s][x.first][0] ||
+          packs[s][x.first][1])
+        continue;
       const int a1 = tx[0].first, b1 = tx[0].second, a2 = tx[1].first, b2 = tx[1].second;
       if (a1 == a2 || b1 == b2) continue;
       for (auto &y : terms[s]) {
         if (y.first == x.first || !needed.count({S.out, y.first}) || done.count(y.first) || y.second.size() != 2)
           continue;
-        if (alphas[s][y.first][0] != 1.0 || alphas[s][y.first][1] != 1.0) continue;
+        if (alphas[s][y.first][0] != 1.0 || alphas[s][y.first][1] != 1.0 || packs[s][y.first][0] ||
+            packs[s][y.first][1])
+          continue;
         std::set<std::pair<int, int>> want = {{a1, b2}, {a2, b1}}, have(y.second.begin(), y.second.end());
         if (want != have) continue;
-        const int ap = operand(s, 0, S.a, a1, a2, 1.0), bp = operand(s, 1, S.b, b1, b2, 1.0);
-        const int am = operand(s, 0, S.a, a1, a2, -1.0), bm = operand(s, 1, S.b, b1, b2, -1.0);
-        P.products.push_back({ap, bp, S.out, x.first, s, phase, 0, 0, 1.0});
-        P.products.push_back({am, bm, S.out, y.first, s, phase, 0, 0, 1.0});
+        const int ap = operand(s, 0, S.a, a1, a2, 1.0, 0), bp = operand(s, 1, S.b, b1, b2, 1.0, 0);
+        const int am = operand(s, 0, S.a, a1, a2, -1.0, 0), bm = operand(s, 1, S.b, b1, b2, -1.0, 0);
+        P.products.push_back({ap, bp, S.out, x.first, s, phase, 0, 0, 1.0, 0});
+        P.products.push_back({am, bm, S.out, y.first, s, phase, 0, 0, 1.0, 0});
         P.unscrambles.push_back({S.out, x.first, y.first, phase});
         done.insert(x.first);
         done.insert(y.first);
@@ -269,9 +284,10 @@ inline Plan build_plan() {
       if (!needed.count({S.out, x.first}) || done.count(x.first)) continue;
       int term = 0;
       for (size_t q = 0; q < x.second.size(); ++q) {
-        const int ab = operand(s, 0, S.a, x.second[q].first, -1, 0.0);
-        const int bb = operand(s, 1, S.b, x.second[q].second, -1, 0.0);
-        P.products.push_back({ab, bb, S.out, x.first, s, phase, term > 0, term, alphas[s][x.first][q]});
+        const int pk = packs[s][x.first][q];
+        const int ab = operand(s, 0, S.a, x.second[q].first, -1, 0.0, pk);
+        const int bb = operand(s, 1, S.b, x.second[q].second, -1, 0.0, pk);
+        P.products.push_back({ab, bb, S.out, x.first, s, phase, term > 0, term, alphas[s][x.first][q], pk});
         ++term;
       }
     }
