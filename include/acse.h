@@ -6,7 +6,8 @@
  *
  *   residual  R^{ij}_{kl} = <psi| [a+_i a+_j a_l a_k, H] |psi>        (Eq. (4))
  *             with the 3-RDM rebuilt by Valdemoro cumulant reconstruction
- *             (Eq. (7) with 3Delta = 0; App. C, Eq. (C5)) and never stored,
+ *             (Eq. (7) with 3Delta = 0; App. C, Eq. (C5)) or, as an option,
+ *             by the Nakatsuji-Yasuda one (Eq. (8)), and never stored,
  *   update    U = 1/2 <[a+a+aa, A]>, A = sum R_m a+a+aa,  2D <- 2D + eps U  (Eq. (9)),
  *   energy    E = Tr(K 2D) with the reduced Hamiltonian K of Eq. (2).
  *
@@ -39,8 +40,10 @@
  * Memory: h, V, d1, d2aa, d2ab and all outputs are DEVICE pointers on the
  * context's device, 16-byte aligned, owned by the caller.  Outputs ending in
  * _host are host pointers.  The library owns only its workspace, allocated in
- * acse_create for a maximum size r_max and released in acse_destroy; it keeps
- * no caller pointer after a call returns.
+ * acse_create for a maximum size r_max (the adjoint, the Euler driver, the
+ * batched residual and the Nakatsuji-Yasuda reconstruction add their own on
+ * their first call, also sized for r_max or the batch) and released in
+ * acse_destroy; it keeps no caller pointer after a call returns.
  *
  * Streams: every call is ordered on the context's HIP stream.  Calls that
  * return a host scalar synchronise that stream before returning; the others
