@@ -123,10 +123,13 @@ typedef struct {
  *                  internal indices) in the call's precision; its combination into the map is FP64.  The
  *                  first NY call allocates its workspace for r_max (about
  *                  (19 r^4 + 44 r^4-sized operand buffers) x 8 bytes: 3.3 GB at
- *                  r_max = 50; ACSE_ERR_NOMEM if that fails).  The adjoint
- *                  (acse_residual_vjp), the quadratic step control of
- *                  acse_solve (which needs it) and the batched residual are
- *                  ACSE_ERR_UNSUPPORTED with it. */
+ *                  r_max = 50; ACSE_ERR_NOMEM if that fails).  In the
+ *                  batched residual each instance takes its reference
+ *                  occupations from its n_alpha (ny_sigma must be NULL) and
+ *                  the NY shares run in order on the context's stream.  The
+ *                  adjoint (acse_residual_vjp) and the quadratic step control
+ *                  of acse_solve (which needs it) are ACSE_ERR_UNSUPPORTED
+ *                  with it. */
 typedef enum { ACSE_RECON_V = 0, ACSE_RECON_NY = 1 } acse_reconstruction;
 
 /* acse_options.flags: run the general-size kernels at every r (the one-index

@@ -405,9 +405,11 @@ class Context:
                                                times))
         return best.value, list(times)
 
-    def residual_batched(self, instances, precision="fp64", tile=-1, flags=0):
+    def residual_batched(self, instances, precision="fp64", tile=-1, flags=0, ny=False):
         """instances: sequence of dicts with h, V, gamma, d2aa, d2ab, N.  One
-        batched call; returns [(R_aa, R_ab, norm2)] in input order."""
+        batched call; returns [(R_aa, R_ab, norm2)] in input order.  ny=True
+        selects the Nakatsuji-Yasuda 3-RDM with each instance's orbitals below
+        N/2 occupied."""
         probs, keep, outs = [], [], []
         for p in instances:
             prob, t = self.problem(p["h"], p["V"], p["gamma"], p["d2aa"], p["d2ab"], p["N"] // 2)
@@ -416,7 +418,7 @@ class Context:
             r = prob.r
             outs.append([torch.empty((r, r, r, r), dtype=torch.float64, device=self.device)
                          for _ in range(2)])
-        n2 = self.residual_batched_raw(probs, self.options(precision, None, tile, flags),
+        n2 = self.residual_batched_raw(probs, self.options(precision, None, tile, flags, True if ny else None),
                                        [o[0] for o in outs], [o[1] for o in outs])
         return [(o[0], o[1], v) for o, v in zip(outs, n2)]
 

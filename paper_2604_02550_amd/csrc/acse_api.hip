@@ -1776,7 +1776,9 @@ acse_status validate_batch(acse_ctx c, int32_t count, const acse_problem *probs,
     acse_status st = validate(c, &probs[i], opts);
     if (st != ACSE_OK) return fail(c, st, "instance " + std::to_string(i) + ": " + c->err);
   }
-  if (c->ny_on) return fail(c, ACSE_ERR_UNSUPPORTED, "the batched residual is built for the Valdemoro reconstruction only");
+  if (c->ny_on && opts->ny_sigma)
+    return fail(c, ACSE_ERR_ARG, "a batch takes each instance's reference occupations from its n_alpha: "
+                                 "ny_sigma must be NULL");
   return ACSE_OK;
 }
 
@@ -1918,8 +1920,22 @@ acse_status run_batched(acse_ctx c, int count, const acse_problem *probs, GemmPr
     HIP_TRY(c, gemm_launch_persistent(prec, cfg, gp, c->hdesc, plan.dprobs, c->stream));
     HIP_TRY(c, hipEventRecord(c->hdesc_done, c->stream));
   }
-  if ((st = fork_sides(c, ns)) != ACSE_OK) return st;
   const ActiveBits none{};
+  if (c->ny_on) {
+    // the NY share uses one workspace per context: the back ends run in order
+    // on the context's stream, each with its instance's reference occupations
+    for (int i : order) {
+      const acse_problem *p = &probs[i];
+      c->ny_sigma.assign(p->r, -1.0);
+      for (int q = 0; q < p->n_alpha; ++q) c->ny_sigma[q] = 1.0;
+      if ((st = map_back(c, p, -1.0, Raa ? Raa[i] : plan.ws[i].Raa, Rab ? Rab[i] : plan.ws[i].Rab, none,
+                         nullptr, nullptr, plan.norms + i, plan.ws[i], plan.ws[i].Aaa, plan.ws[i].Aab,
+                         prec)) != ACSE_OK)
+        return st;
+    }
+    return ACSE_OK;
+  }
+  if ((st = fork_sides(c, ns)) != ACSE_OK) return st;
   for (int i : order) {
     StreamSwap sw(c, c->side[lane[i]]);
     if ((st = map_back(c, &probs[i], -1.0, Raa ? Raa[i] : plan.ws[i].Raa,
@@ -1965,6 +1981,7 @@ extern "C" acse_status acse_autotune_batched(acse_ctx ctx, int32_t count, const 
                                              double *times_ms) {
   acse_status st = validate_batch(ctx, count, probs, opts);
   if (st != ACSE_OK) return st;
+  ctx->ny_on = false;  // the tile choice concerns the Valdemoro products
   if (!best_tile) return fail(ctx, ACSE_ERR_ARG, "best_tile is NULL");
   HIP_TRY(ctx, hipSetDevice(ctx->device));
   const GemmPrec prec = prec_of(opts);

@@ -21,8 +21,10 @@ test_oracle_ny.py).
 * FP32 and split-BF16 block products (the combination FP64) at the bars of
   the Valdemoro mixed modes, 1e-5 and 5e-5 of the largest element, on the
   residual and on the step's update.
-* Rejected combinations: the adjoint, the quadratic control, the batched
-  residual, sigma entries other than +1 / -1.
+* The batched residual with the NY 3-RDM (instances of r = 6, 9, 13 in one
+  call) against the oracle per instance.
+* Rejected combinations: the adjoint, the quadratic control, an explicit
+  sigma array in a batch, sigma entries other than +1 / -1.
 * Edges: r = 2 and 3; the step with the active-active mask on the
   general-size kernels; the update map on an anti-Hermitian direction that is
   not a residual; the backtracking control (rejected trials) with the input
@@ -190,13 +192,16 @@ def test_ny_rejected_combinations(acse):
     import torch
     p = correlated(4, 4, 0)
     ctx = acse.Context(r_max=4)
+    z = [torch.zeros((4, 4, 4, 4), dtype=torch.float64, device="cuda") for _ in range(5)]
     try:
         with pytest.raises(acse.AcseError, match="ny_sigma"):
             ctx.residual(p["h"], p["V"], p["gamma"], p["d2aa"], p["d2ab"], 2, sigma=[1, 0, -1, -1])
+        bp, bkeep = ctx.problem(p["h"], p["V"], p["gamma"], p["d2aa"], p["d2ab"], 2)
+        with pytest.raises(acse.AcseError, match="ny_sigma must be NULL"):
+            ctx.residual_batched_raw([bp], ctx.options("fp64", sigma=[1, 1, -1, -1]), [z[0]], [z[1]])
         with pytest.raises(acse.AcseError, match="quadratic"):
             ctx.solve(p["h"], p["V"], p["gamma"], p["d2aa"], p["d2ab"], 2, control="quadratic", sigma=True)
         prob, keep = ctx.problem(p["h"], p["V"], p["gamma"], p["d2aa"], p["d2ab"], 2)
-        z = [torch.zeros((4, 4, 4, 4), dtype=torch.float64, device="cuda") for _ in range(5)]
         zs = [torch.zeros((4, 4), dtype=torch.float64, device="cuda") for _ in range(2)]
         opts = ctx.options("fp64", sigma=True)
         with pytest.raises(acse.AcseError, match="adjoint"):
@@ -361,3 +366,22 @@ def test_ny_backtracking_solve_and_input_check(acse):
         assert abs(gf - of) <= 1e-10 * of
     for key in ("d2aa", "d2ab"):
         assert np.abs(g[key].cpu().numpy() - o[key]).max() <= 1e-10 * np.abs(o[key]).max(), key
+
+
+def test_ny_batched_residual(acse):
+    insts = [correlated(6, 4, 61), correlated(9, 8, 62), correlated(13, 8, 63)]
+    print("[ny] batched residual r=6,9,13", flush=True)
+    ctx = acse.Context(r_max=13)
+    try:
+        got = ctx.residual_batched(insts, ny=True)
+        plain = ctx.residual_batched(insts)
+    finally:
+        ctx.close()
+    for q, (Raa, Rab, n2), (Vaa, Vab, _) in zip(insts, got, plain):
+        sig = sigma_of(q, "prefix")
+        oaa, oab, on2 = ost.residual(q["h"], q["V"], q["N"], q["gamma"], q["d2aa"], q["d2ab"], sigma=sig)
+        scale = max(np.abs(oaa).max(), np.abs(oab).max())
+        assert np.abs(Raa.cpu().numpy() - oaa).max() <= 1e-10 * scale
+        assert np.abs(Rab.cpu().numpy() - oab).max() <= 1e-10 * scale
+        assert abs(n2 - on2) <= 1e-10 * on2
+        assert np.abs((Raa - Vaa).cpu().numpy()).max() > 1e-6 * scale  # the NY share is there
