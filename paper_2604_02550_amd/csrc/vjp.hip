@@ -36,7 +36,7 @@ struct VOutBF16x3 {
 // dst[row][col] (rows x ld) = c1 src1[idx1] + c2 src2[idx2] for row, col < r^2,
 // zero in the padding; row = (a, b), col = (c, d), idx = a s0 + b s1 + c s2 + d s3.
 // One block per destination row (32-bit index arithmetic within the row).
-constexpr int kPermU = 8;
+constexpr int kPermU = 10;
 
 template <class O>
 __global__ void __launch_bounds__(256)
