@@ -478,23 +478,23 @@ acse_status ensure_ny_ws(acse_ctx c) {
   return ACSE_OK;
 }
 
-acse_status ny_share_run(acse_ctx c, const acse_problem *p, GemmPrec prec, const double *Xaa,
+acse_status ny_share_run(acse_ctx c, const acse_problem *p, GemmPrec prec, int tile, const double *Xaa,
                          const double *Xab, double *Saa, double *Sab);
 
 // The NY share of F(X): S_aa -= C_aa, S_ab -= C_ab (C = B - B(k<->l), B the
 // 3-cumulant's share of the 3-RDM contraction), on the plan of ny_plan.h.  No
 // C++ exception (an allocation of the plan's containers, a plan lookup)
 // leaves through the C interface.
-acse_status ny_share(acse_ctx c, const acse_problem *p, GemmPrec prec, const double *Xaa, const double *Xab,
-                     double *Saa, double *Sab) {
+acse_status ny_share(acse_ctx c, const acse_problem *p, GemmPrec prec, int tile, const double *Xaa,
+                     const double *Xab, double *Saa, double *Sab) {
   try {
-    return ny_share_run(c, p, prec, Xaa, Xab, Saa, Sab);
+    return ny_share_run(c, p, prec, tile, Xaa, Xab, Saa, Sab);
   } catch (const std::exception &e) {
     return fail(c, ACSE_ERR_NOMEM, std::string("Nakatsuji-Yasuda share: ") + e.what());
   }
 }
 
-acse_status ny_share_run(acse_ctx c, const acse_problem *p, GemmPrec prec, const double *Xaa,
+acse_status ny_share_run(acse_ctx c, const acse_problem *p, GemmPrec prec, int tile, const double *Xaa,
                          const double *Xab, double *Saa, double *Sab) {
   const int r = p->r;
   hipStream_t s = c->stream;
@@ -533,7 +533,7 @@ acse_status ny_share_run(acse_ctx c, const acse_problem *p, GemmPrec prec, const
   const int64_t pst[4] = {r * ld, ld, r, 1};  // staging: the operand layout in FP64
   int ns = 0;
   const ny::Stage *stg = ny::stages(&ns);
-  const int cfg = map_cfg(c, prec, r, -1);
+  const int cfg = map_cfg(c, prec, r, tile);
   const int kp = gemm_kp(prec, (int)r2, (int)ld);
   const int64_t ld_lt = ld_pair_lt(r);
   const int kp_lt = gemm_kp(prec, npair_lt(r), (int)ld_lt);
@@ -649,7 +649,7 @@ acse_status ny_share_run(acse_ctx c, const acse_problem *p, GemmPrec prec, const
 acse_status map_back(acse_ctx c, const acse_problem *p, double sigma, double *Oaa, double *Oab,
                      const ActiveBits &act, double *Maa, double *Mab, double *norm_out,
                      Workspace &w, const double *Xaa = nullptr, const double *Xab = nullptr,
-                     GemmPrec prec = GEMM_F64) {
+                     GemmPrec prec = GEMM_F64, int tile = -1) {
   const int r = p->r;
   hipStream_t s = c->stream;
   {
@@ -659,7 +659,7 @@ acse_status map_back(acse_ctx c, const acse_problem *p, double sigma, double *Oa
   }
   if (c->ny_on) {
     if (!Xaa || !Xab) return fail(c, ACSE_ERR_UNSUPPORTED, "the NY share needs the map's X");
-    acse_status st = ny_share(c, p, prec, Xaa, Xab, w.Saa, w.Sab);
+    acse_status st = ny_share(c, p, prec, tile, Xaa, Xab, w.Saa, w.Sab);
     if (st != ACSE_OK) return st;
   }
   StageTimer t4b(c, 4);
@@ -691,7 +691,7 @@ acse_status run_map(acse_ctx c, const acse_problem *p, GemmPrec prec, int cfg, c
     StageTimer t3(c, 3);
     HIP_TRY(c, gemm_launch(prec, use_cfg, batch, c->stream));
   }
-  return map_back(c, p, sigma, Oaa, Oab, act, Maa, Mab, w.scal + slot, w, Xaa, Xab, prec);
+  return map_back(c, p, sigma, Oaa, Oab, act, Maa, Mab, w.scal + slot, w, Xaa, Xab, prec, cfg);
 }
 
 ActiveBits make_bits(const acse_options *o, int r, bool *any) {
@@ -1930,7 +1930,7 @@ acse_status run_batched(acse_ctx c, int count, const acse_problem *probs, GemmPr
       for (int q = 0; q < p->n_alpha; ++q) c->ny_sigma[q] = 1.0;
       if ((st = map_back(c, p, -1.0, Raa ? Raa[i] : plan.ws[i].Raa, Rab ? Rab[i] : plan.ws[i].Rab, none,
                          nullptr, nullptr, plan.norms + i, plan.ws[i], plan.ws[i].Aaa, plan.ws[i].Aab,
-                         prec)) != ACSE_OK)
+                         prec, cfg)) != ACSE_OK)
         return st;
     }
     return ACSE_OK;

@@ -385,3 +385,23 @@ def test_ny_batched_residual(acse):
         assert np.abs(Rab.cpu().numpy() - oab).max() <= 1e-10 * scale
         assert abs(n2 - on2) <= 1e-10 * on2
         assert np.abs((Raa - Vaa).cpu().numpy()).max() > 1e-6 * scale  # the NY share is there
+
+
+@pytest.mark.parametrize("tile", [0, 1, 2])
+def test_ny_every_tile_config(acse, tile):
+    """acse_options.tile selects the tile configuration of the NY block
+    products as of the Valdemoro ones."""
+    r, N = 13, 8
+    p = correlated(r, N, 71)
+    sig = sigma_of(p, "prefix")
+    print(f"[ny] residual r={r} tile={tile}", flush=True)
+    oaa, oab, on2 = ost.residual(p["h"], p["V"], N, p["gamma"], p["d2aa"], p["d2ab"], sigma=sig)
+    ctx = acse.Context(r_max=r)
+    try:
+        Raa, Rab, n2 = ctx.residual(p["h"], p["V"], p["gamma"], p["d2aa"], p["d2ab"], N // 2, tile=tile, sigma=True)
+    finally:
+        ctx.close()
+    scale = max(np.abs(oaa).max(), np.abs(oab).max())
+    assert np.abs(Raa.cpu().numpy() - oaa).max() <= 1e-10 * scale
+    assert np.abs(Rab.cpu().numpy() - oab).max() <= 1e-10 * scale
+    assert abs(n2 - on2) <= 1e-10 * on2
