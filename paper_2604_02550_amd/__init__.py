@@ -315,7 +315,8 @@ class Context:
         taken, the lambda trajectory) is written to ``path`` (numpy .npz of
         plain arrays, replaced atomically).  If ``path`` exists the iteration
         resumes from it: the state it holds replaces d1, d2aa and d2ab, and it
-        must have been written for the same h, V and electron count.  Each chunk
+        must have been written for the same h, V, electron count and
+        reconstruction (``sigma``, passed on to ``solve``).  Each chunk
         starts from the state the previous one returned, so the result is the
         one an uninterrupted ``solve`` reaches.  Returns the dict of the last
         chunk with ``iterations`` counting every chunk's steps, ``trajectory``
@@ -327,6 +328,9 @@ class Context:
         for x in (h, V):
             tag.update(np.ascontiguousarray(_host64(x)).tobytes())
         tag.update(str(int(n_alpha)).encode())
+        sigma = kw.get("sigma")
+        if sigma is not None and sigma is not False:
+            tag.update(b"NY:" + (b"default" if sigma is True else bytes(str([int(x) for x in sigma]), "ascii")))
         tag = tag.hexdigest()
         done, resumed = 0, False
         traj = None

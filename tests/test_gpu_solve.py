@@ -202,6 +202,8 @@ def test_solve_checkpoint_resume(acse, ctx, tmp_path):
     for (l1, e1, g1), (l2, e2, g2) in zip(traj, ref):
         assert abs(l1 - l2) <= 1e-15 and abs(e1 - e2) <= 1e-12 * abs(e2) and abs(g1 - g2) <= 1e-12
     assert [round(t[0] / 1e-3) for t in traj] == [0, 1, 2, 3, 4]
-    # a file written for another Hamiltonian is refused
+    # a file written for another Hamiltonian, or for another reconstruction, is refused
     with pytest.raises(ValueError, match="another problem"):
         ctx.solve_checkpointed(p["h"] * 1.01, *args[1:], path=path, every=1, max_iter=6, eps=1e-3)
+    with pytest.raises(ValueError, match="another problem"):
+        ctx.solve_checkpointed(*args, path=path, every=1, max_iter=6, eps=1e-3, sigma=True)
