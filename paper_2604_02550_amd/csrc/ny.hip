@@ -62,6 +62,8 @@ k_ny_trace_y(int r, int64_t ld, const double *__restrict__ W0, const double *__r
   Y[e] = acc;
 }
 
+constexpr int kKB = 4;  // k values per thread in k_ny_bsum
+
 // One block per (i,j) slab: Y and the slab SD(b)[i,j,:,:] in LDS, so the
 // r-term sums of T_pl read LDS; the other terms are read along (k,l).
 __global__ void __launch_bounds__(256) k_ny_bsum(int r, NyCombineArgs a) {
@@ -79,13 +81,27 @@ __global__ void __launch_bounds__(256) k_ny_bsum(int r, NyCombineArgs a) {
     __syncthreads();
     for (int64_t x = threadIdx.x; x < r2; x += 256) ss[(x / r) * rp + x % r] = a.sd[b][base + x];
     __syncthreads();
-    for (int64_t x = threadIdx.x; x < r2; x += 256) {
-      const int k = (int)(x / r), l = (int)(x % r);
-      const double *y = ys + k * rp;
-      double pl = 0.0;
-      for (int q = 0; q < r; ++q) pl += y[q] * ss[q * rp + l];
-      a.B[b][base + x] = 4.0 * (a.il[b][base + x] - a.il[bs][jib + x] + pl - 2.0 * a.ir[b][base + x] +
-                                2.0 * a.ir[bs][jib + x] - 2.0 * a.pr[b][base + x]);
+    // a thread takes kKB consecutive k for one l: each slab value read from
+    // LDS serves kKB sums (the Y reads are shared by the threads of a k group)
+    const int nkb = (r + kKB - 1) / kKB;
+    for (int task = threadIdx.x; task < r * nkb; task += 256) {
+      const int l = task % r, k0 = (task / r) * kKB;
+      double pl[kKB];
+#pragma unroll
+      for (int u = 0; u < kKB; ++u) pl[u] = 0.0;
+      for (int q = 0; q < r; ++q) {
+        const double sv = ss[q * rp + l];
+#pragma unroll
+        for (int u = 0; u < kKB; ++u) pl[u] += ys[min(k0 + u, r - 1) * rp + q] * sv;
+      }
+#pragma unroll
+      for (int u = 0; u < kKB; ++u) {
+        const int k = k0 + u;
+        if (k >= r) break;
+        const int64_t x = (int64_t)k * r + l;
+        a.B[b][base + x] = 4.0 * (a.il[b][base + x] - a.il[bs][jib + x] + pl[u] - 2.0 * a.ir[b][base + x] +
+                                  2.0 * a.ir[bs][jib + x] - 2.0 * a.pr[b][base + x]);
+      }
     }
   }
 }
