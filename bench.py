@@ -8,11 +8,12 @@ Each step starts from the same input state: the 1-/2-RDM blocks are restored
 on the device from a pristine copy inside the timed region (one r^4 device copy
 per block, negligible next to the contractions).
 
-Prints one JSON line.  ``value`` = residual evaluations per second = steps per
-second (one residual per step; the update map, step and energy are inside the
-same timed step).  The residual-only rate of the same kernels is reported
-beside it, and the FP32 / split-BF16 modes are timed and checked against the
-stored FP64 oracle values.
+Prints one JSON line.  ``value`` = steps per second of the first mode in
+``--modes`` (one step = one ``acse_step``: the residual, the update map, the
+Euler step and the energy).  ``residual_evals_per_s`` is the residual-only
+rate (``acse_residual`` alone) of the same kernels.  Every mode is timed and
+its one-step energy checked against the stored FP64 oracle values;
+``accuracy_gate`` says per mode whether |dE| < 1e-7 Eh holds.
 
     python bench.py [--steps K] [--warmup W] [--modes fp64,fp32,bf16x3] [--no-cpu-baseline]
 """
@@ -283,6 +284,60 @@ def bench_ny(acse, ctx, prob, work, pristine, torch, stream, steps, warmup, eps,
                 energy_identity_rel=abs((E1 - E0) + eps * n2) / (eps * n2))
 
 
+def cpu_model():
+    """CPU model string of the host (the 'model name' line of /proc/cpuinfo)."""
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    import platform
+    return platform.processor() or "unknown"
+
+
+def time_oracle(fn, reps=3, warmup=1):
+    """Median wall time of `reps` calls after `warmup` untimed ones."""
+    for _ in range(warmup):
+        fn()
+    ts = []
+    for _ in range(reps):
+        t0 = time.perf_counter()
+        fn()
+        ts.append(time.perf_counter() - t0)
+    return float(np.median(ts)), ts
+
+
+def cpu_baseline(p, gen):
+    """The FP64 oracle's residual (tier B, dense spin-orbital products of about
+    384 r^6 flops; a correctness oracle, not a tuned CPU code) on this host:
+    every usable core, 1 warm-up and the median of 3 at the bench workload, plus
+    one 1-thread call on the r = 30, N = 20 workload for scale."""
+    import torch
+    from oracle import step as ost
+
+    usable = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else os.cpu_count()
+    before = torch.get_num_threads()
+    torch.set_num_threads(usable)
+    args = (p["h"], p["V"], p["N"], p["gamma"], p["d2aa"], p["d2ab"])
+    med, ts = time_oracle(lambda: ost.residual(*args))
+    torch.set_num_threads(1)
+    q = gen.named("r30")
+    t1, _ = time_oracle(lambda: ost.residual(q["h"], q["V"], q["N"], q["gamma"], q["d2aa"], q["d2ab"]),
+                        reps=1, warmup=0)
+    torch.set_num_threads(before)
+    r = p["r"]
+    return {"value": 1.0 / med, "unit": "residual evals/s", "cores": usable, "kind": "oracle",
+            "sample": f"FP64 oracle residual at r={r}, N={p['N']} (spin-orbital factorised form, about "
+                      f"384 r^6 = {384 * r ** 6:.2e} flop): median of 3 after 1 warm-up on {usable} threads "
+                      f"({', '.join(f'{t:.2f}' for t in ts)} s)",
+            "cpu_model": cpu_model(), "os_cpu_count": os.cpu_count(),
+            "oracle_gflops": 384 * r ** 6 / med / 1e9,
+            "one_thread_r30": {"seconds": t1, "evals_per_s": 1.0 / t1,
+                               "sample": "one FP64 oracle residual at r=30, N=20 on 1 thread"}}
+
+
 def src_hash():
     h = hashlib.sha256()
     for path in TRAFFIC_SRCS:
@@ -380,6 +435,7 @@ def main():
                    (("R_aa", R[0]), ("R_ab", R[1]), ("U_aa", U[0]), ("U_ab", U[1]))}
             err = dict(
                 dE=abs(E1 - golden["energy1"]),
+                meets_dE_1em7=bool(abs(E1 - golden["energy1"]) < 1e-7),
                 dE_rel_to_step=abs(E1 - golden["energy1"]) / abs(golden["energy1"] - golden["energy0"]),
                 norm2_rel=abs(n2 - golden["norm2"]) / golden["norm2"],
             )
@@ -411,7 +467,7 @@ def main():
     line = {
         "metric": "ACSE residual evals/s + TFLOP/s at r=50: FP64 vs mixed at |dE|<1e-7 Eh",
         "value": hr["steps_per_s"],
-        "unit": "residual evals/s",
+        "unit": "steps/s (one acse_step: residual, update map, Euler step, energy)",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
@@ -430,7 +486,11 @@ def main():
                      "traffic": traffic,
                      "kernel": gemm_kernel_name(head, hr["tile_config"]) +
                                " (grouped: 3 ph + 3 packed pp products per launch)"},
-        "residual_only_evals_per_s": hr["residual_evals_per_s"],
+        "residual_evals_per_s": hr["residual_evals_per_s"],
+        "accuracy_gate": {m: {"dE_Eh": (v["error_vs_oracle"] or {}).get("dE"),
+                              "meets_dE_1e-7": (v["error_vs_oracle"] or {}).get("meets_dE_1em7"),
+                              "steps_per_s": v["steps_per_s"], "residual_evals_per_s": v["residual_evals_per_s"]}
+                          for m, v in results.items()},
         "modes": results,
     }
     if args.solve_controls:
@@ -450,14 +510,9 @@ def main():
     if not args.no_cpu_baseline:
         import torch as _t
         from oracle import step as ost
-        threads = _t.get_num_threads()
-        t0 = time.perf_counter()
-        ost.residual(p["h"], p["V"], p["N"], p["gamma"], p["d2aa"], p["d2ab"])
-        dt = time.perf_counter() - t0
-        line["cpu_baseline"] = {"value": 1.0 / dt, "unit": "residual evals/s", "cores": threads,
-                                "kind": "oracle",
-                                "sample": f"one FP64 oracle residual at r={r}, N={N} (spin-orbital "
-                                          f"factorised form, {dt:.1f} s)"}
+        line["cpu_baseline"] = cpu_baseline(p, gen)
+        threads = line["cpu_baseline"]["cores"]
+        _t.set_num_threads(threads)
         if args.ny_steps > 0 and "fp64" in line.get("nakatsuji_yasuda", {}):
             sigma = np.where(np.arange(r) < N // 2, 1.0, -1.0)
             t0 = time.perf_counter()

@@ -40,7 +40,7 @@ import numpy as np
 
 from . import adjoint, rdm
 from .residual import residual_map
-from .step import active_mask
+from .step import active_mask, restore_traces
 
 FIXED, BACKTRACK, QUADRATIC = 0, 1, 2
 STOP_MAX_ITER, STOP_CONVERGED, STOP_ENERGY_ROSE, STOP_NORM_ROSE = 0, 1, 2, 3
@@ -55,12 +55,7 @@ def _residual(K, gamma, d2aa, d2ab, sigma_so=None):
 def _trial(K, N, d2aa, d2ab, uaa, uab, eps):
     """2D' = (2D + eps U) rescaled per block to the trace of 2D; gamma'; E'."""
     r = d2aa.shape[0]
-    a = d2aa + eps * uaa
-    b = d2ab + eps * uab
-    t0aa, t0ab = rdm.block_traces(d2aa, d2ab)
-    t1aa, t1ab = rdm.block_traces(a, b)
-    a = a * (t0aa / t1aa)
-    b = b * (t0ab / t1ab)
+    a, b, _ = restore_traces(d2aa + eps * uaa, d2ab + eps * uab, rdm.block_traces(d2aa, d2ab))
     _, d2 = rdm.blocks_to_spin_orbital(np.eye(r), a, b)
     gamma = rdm.contract_to_1rdm(d2, N)[:r, :r]
     return a, b, gamma, float(np.sum(K * d2))

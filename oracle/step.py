@@ -38,6 +38,17 @@ def active_mask(active, r):
     return ~all4
 
 
+def restore_traces(d2aa, d2ab, traces):
+    """Trace restoration after the update: each block is multiplied by the ratio
+    of the trace it must keep (``traces`` = (Tr 2D_aa, Tr 2D_ab) of the input
+    state, App. A) to the trace it has now, so Tr 2D_aa and Tr 2D_ab return to
+    their input values and nothing else changes shape.  Returns the rescaled
+    blocks and the two factors."""
+    t1aa, t1ab = rdm.block_traces(d2aa, d2ab)
+    s_aa, s_ab = traces[0] / t1aa, traces[1] / t1ab
+    return d2aa * s_aa, d2ab * s_ab, (s_aa, s_ab)
+
+
 def norm2_spin_orbital(t4):
     return float(np.sum(np.asarray(t4) ** 2))
 
@@ -76,19 +87,15 @@ def step(h, V, N, gamma, d2aa, d2ab, eps, active=None, keep_spin_orbital=False, 
     U = residual_map(Rm, d1, d2, hermitian=False, sigma_so=sso).numpy()
     raa, rab = rdm.spin_orbital_to_blocks(R)
     uaa, uab = rdm.spin_orbital_to_blocks(U)
-    d2aa_1 = d2aa + eps * uaa
-    d2ab_1 = d2ab + eps * uab
-    t0aa, t0ab = rdm.block_traces(d2aa, d2ab)
-    t1aa, t1ab = rdm.block_traces(d2aa_1, d2ab_1)
-    d2aa_1 = d2aa_1 * (t0aa / t1aa)
-    d2ab_1 = d2ab_1 * (t0ab / t1ab)
+    d2aa_1, d2ab_1, scale = restore_traces(d2aa + eps * uaa, d2ab + eps * uab,
+                                           rdm.block_traces(d2aa, d2ab))
     _, d2_1 = rdm.blocks_to_spin_orbital(gamma, d2aa_1, d2ab_1)
     gamma_1 = rdm.contract_to_1rdm(d2_1, N)[:r, :r]
     e1 = float(np.sum(K * d2_1))
     out = dict(R_aa=raa, R_ab=rab, norm2=n2, U_aa=uaa, U_ab=uab,
                d2aa=d2aa_1, d2ab=d2ab_1, gamma=gamma_1, energy=e1,
                energy0=float(np.sum(K * d2)),
-               trace_scale=(t0aa / t1aa, t0ab / t1ab))
+               trace_scale=scale)
     if keep_spin_orbital:
         out.update(R=R, U=U, Rm=Rm, K=K, d1=d1, d2=d2)
     return out

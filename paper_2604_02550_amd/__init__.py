@@ -138,12 +138,67 @@ def _dev(t, device):
     return t.to(device=device, dtype=torch.float64).contiguous()
 
 
+def _shape(x):
+    if isinstance(x, torch.Tensor):
+        return tuple(x.shape)
+    import numpy as np
+    return np.shape(x)
+
+
+def _numel(x):
+    n = 1
+    for d in _shape(x):
+        n *= int(d)
+    return n
+
+
+def check_problem_shapes(h, V, d1, d2aa, d2ab):
+    """r from h; ValueError unless h and d1 are r x r and V, d2aa, d2ab hold r^4
+    elements each (the library reads exactly that many through each pointer)."""
+    sh = _shape(h)
+    if len(sh) != 2 or sh[0] != sh[1] or sh[0] < 1:
+        raise ValueError(f"h must be a square r x r array, got shape {sh}")
+    r = int(sh[0])
+    if _shape(d1) != (r, r):
+        raise ValueError(f"d1 must have shape ({r}, {r}), got {_shape(d1)}")
+    for name, x in (("V", V), ("d2aa", d2aa), ("d2ab", d2ab)):
+        if _numel(x) != r ** 4:
+            raise ValueError(f"{name} must hold r^4 = {r ** 4} elements (r = {r}), got shape {_shape(x)}")
+    return r
+
+
+def _check_dev4(t, r, name, device):
+    """A caller array the library reads or writes as r^4 FP64 values on the device."""
+    if not isinstance(t, torch.Tensor):
+        raise ValueError(f"{name} must be a torch tensor on {device}")
+    if t.dtype != torch.float64 or t.device != device or not t.is_contiguous():
+        raise ValueError(f"{name} must be a contiguous float64 tensor on {device}")
+    if t.numel() != r ** 4:
+        raise ValueError(f"{name} must hold r^4 = {r ** 4} elements (r = {r}), got shape {tuple(t.shape)}")
+
+
+def _check_dev2(t, r, name, device):
+    if not isinstance(t, torch.Tensor) or t.dtype != torch.float64 or t.device != device \
+            or not t.is_contiguous():
+        raise ValueError(f"{name} must be a contiguous float64 tensor on {device}")
+    if t.numel() != r * r:
+        raise ValueError(f"{name} must hold r^2 = {r * r} elements (r = {r}), got shape {tuple(t.shape)}")
+
+
+def _check_opts(opts, r):
+    """The host arrays of the options (active mask, NY occupations) must cover r orbitals."""
+    for name, n in getattr(opts, "_lens", {}).items():
+        if n is not None and n != r:
+            raise ValueError(f"options.{name} has {n} entries, the problem has r = {r} orbitals")
+
+
 class Context:
     """One library context: a device, a stream and workspace for r <= r_max."""
 
     def __init__(self, r_max, device=0, stream=None):
-        self.device = torch.device("cuda", device) if isinstance(device, int) else torch.device(device)
-        idx = self.device.index or 0
+        dev = torch.device("cuda", device) if isinstance(device, int) else torch.device(device)
+        idx = dev.index or 0
+        self.device = torch.device("cuda", idx)
         self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
         h = ctypes.c_void_p()
         st = _lib.acse_create(ctypes.byref(h), idx, ctypes.c_void_p(self.stream.cuda_stream),
@@ -181,6 +236,7 @@ class Context:
     def autotune_raw(self, prob, opts):
         """Times every GEMM tile configuration on this problem and caches the best
         for (r, precision); returns (best index, [ms per configuration])."""
+        _check_opts(opts, prob.r)
         best = ctypes.c_int32(-1)
         times = (ctypes.c_double * NUM_TILE_CONFIGS)()
         self._check(_lib.acse_autotune(self._h, ctypes.byref(prob), ctypes.byref(opts),
@@ -193,8 +249,8 @@ class Context:
 
     def problem(self, h, V, d1, d2aa, d2ab, n_alpha, n_beta=None):
         """Device copies (float64, contiguous) and the ctypes problem struct."""
+        r = check_problem_shapes(h, V, d1, d2aa, d2ab)
         t = [_dev(x, self.device) for x in (h, V, d1, d2aa, d2ab)]
-        r = t[0].shape[0]
         prob = Problem(r, int(n_alpha), int(n_alpha if n_beta is None else n_beta),
                        *[x.data_ptr() for x in t])
         return prob, t
@@ -218,9 +274,14 @@ class Context:
                 sig = ctypes.cast(keep_sig, ctypes.c_void_p)
         o = Options(prec, act, int(tile), int(flags), recon, sig)
         o._keep = (keep, keep_sig)
+        o._lens = {"active": None if keep is None else len(keep),
+                   "ny_sigma": None if keep_sig is None else len(keep_sig)}
         return o
 
     def residual_raw(self, prob, opts, R_aa, R_ab, want_norm=True):
+        _check_opts(opts, prob.r)
+        for name, t in (("R_aa", R_aa), ("R_ab", R_ab)):
+            _check_dev4(t, prob.r, name, self.device)
         n2 = ctypes.c_double(0.0)
         self._check(_lib.acse_residual(self._h, ctypes.byref(prob), ctypes.byref(opts), _ptr(R_aa),
                                        _ptr(R_ab), ctypes.byref(n2) if want_norm else None))
@@ -239,6 +300,9 @@ class Context:
                    sigma=None):
         """U = 1/2 <[a+a+aa, sum X a+a+aa]> for anti-Hermitian X (Eq. (9))."""
         prob, keep = self.problem(h, V, d1, d2aa, d2ab, n_alpha)
+        for name, x in (("X_aa", X_aa), ("X_ab", X_ab)):
+            if _numel(x) != prob.r ** 4:
+                raise ValueError(f"{name} must hold r^4 = {prob.r ** 4} elements, got shape {_shape(x)}")
         X_aa, X_ab = _dev(X_aa, self.device), _dev(X_ab, self.device)
         U_aa = torch.empty_like(X_aa)
         U_ab = torch.empty_like(X_ab)
@@ -259,6 +323,10 @@ class Context:
         return self.energy_raw(prob)
 
     def step_raw(self, prob, eps, opts, R_aa=None, R_ab=None, U_aa=None, U_ab=None, want=True):
+        _check_opts(opts, prob.r)
+        for name, t in (("R_aa", R_aa), ("R_ab", R_ab), ("U_aa", U_aa), ("U_ab", U_ab)):
+            if t is not None:
+                _check_dev4(t, prob.r, name, self.device)
         e = ctypes.c_double(0.0)
         n2 = ctypes.c_double(0.0)
         self._check(_lib.acse_step(self._h, ctypes.byref(prob), float(eps), ctypes.byref(opts),
@@ -284,6 +352,7 @@ class Context:
 
     def solve_raw(self, prob, opts, sopts, capacity=256):
         """acse_solve on a prepared problem; returns (SolveResult, [Trial])."""
+        _check_opts(opts, prob.r)
         res = SolveResult()
         hist = (Trial * max(1, capacity))()
         self._check(_lib.acse_solve(self._h, ctypes.byref(prob), ctypes.byref(opts), ctypes.byref(sopts),
@@ -315,29 +384,22 @@ class Context:
         taken, the lambda trajectory) is written to ``path`` (numpy .npz of
         plain arrays, replaced atomically).  If ``path`` exists the iteration
         resumes from it: the state it holds replaces d1, d2aa and d2ab, and it
-        must have been written for the same h, V, electron count and
-        reconstruction (``sigma``, passed on to ``solve``).  Each chunk
+        must have been written for the same h, V, electron count and options
+        that change the iteration (``checkpoint_tag``; reconstruction, precision,
+        active mask, step control and its limits, de_tol), else ValueError.  Each chunk
         starts from the state the previous one returned, so the result is the
         one an uninterrupted ``solve`` reaches.  Returns the dict of the last
         chunk with ``iterations`` counting every chunk's steps, ``trajectory``
         (see ``trajectory``) and ``resumed``."""
-        import hashlib
         import numpy as np
 
-        tag = hashlib.sha256()
-        for x in (h, V):
-            tag.update(np.ascontiguousarray(_host64(x)).tobytes())
-        tag.update(str(int(n_alpha)).encode())
-        sigma = kw.get("sigma")
-        if sigma is not None and sigma is not False:
-            tag.update(b"NY:" + (b"default" if sigma is True else bytes(str([int(x) for x in sigma]), "ascii")))
-        tag = tag.hexdigest()
+        tag = checkpoint_tag(h, V, n_alpha, **kw)
         done, resumed = 0, False
         traj = None
         if os.path.exists(path):
             with np.load(path, allow_pickle=False) as z:
                 if str(z["tag"]) != tag:
-                    raise ValueError(f"{path} was written for another problem")
+                    raise ValueError(f"{path} was written for another problem or other iteration options")
                 d1, d2aa, d2ab = z["d1"], z["d2aa"], z["d2ab"]
                 eps = float(z["eps"])
                 done = int(z["iterations"])
@@ -374,6 +436,13 @@ class Context:
         return dict(out, iterations=done, trajectory=traj, resumed=resumed)
 
     def residual_vjp_raw(self, prob, opts, Rbar_aa, Rbar_ab, h_bar, V_bar, d1_bar, d2aa_bar, d2ab_bar):
+        _check_opts(opts, prob.r)
+        r = prob.r
+        for name, t in (("Rbar_aa", Rbar_aa), ("Rbar_ab", Rbar_ab), ("V_bar", V_bar), ("d2aa_bar", d2aa_bar),
+                        ("d2ab_bar", d2ab_bar)):
+            _check_dev4(t, r, name, self.device)
+        for name, t in (("h_bar", h_bar), ("d1_bar", d1_bar)):
+            _check_dev2(t, r, name, self.device)
         self._check(_lib.acse_residual_vjp(self._h, ctypes.byref(prob), ctypes.byref(opts),
                                            _ptr(Rbar_aa), _ptr(Rbar_ab), _ptr(h_bar), _ptr(V_bar),
                                            _ptr(d1_bar), _ptr(d2aa_bar), _ptr(d2ab_bar)))
@@ -383,6 +452,9 @@ class Context:
         """Cotangents (h, V, d1, d2aa, d2ab) of <Rbar, R> for the residual of Eq. (4),
         projected onto the symmetry subspace of each input."""
         prob, keep = self.problem(h, V, d1, d2aa, d2ab, n_alpha)
+        for name, x in (("Rbar_aa", Rbar_aa), ("Rbar_ab", Rbar_ab)):
+            if _numel(x) != prob.r ** 4:
+                raise ValueError(f"{name} must hold r^4 = {prob.r ** 4} elements, got shape {_shape(x)}")
         rb = [_dev(x, self.device) for x in (Rbar_aa, Rbar_ab)]
         out = [torch.empty_like(x) for x in keep]
         self.residual_vjp_raw(prob, self.options(precision, None, tile, flags), *rb, *out)
@@ -392,6 +464,12 @@ class Context:
         """probs: sequence of Problem; R_aa/R_ab: sequences of device tensors.
         Returns the list of ||R_i||^2 (or None)."""
         n = len(probs)
+        if len(R_aa) != n or len(R_ab) != n:
+            raise ValueError("one R_aa and one R_ab array per instance")
+        for q, prob in enumerate(probs):
+            _check_opts(opts, prob.r)
+            _check_dev4(R_aa[q], prob.r, f"R_aa[{q}]", self.device)
+            _check_dev4(R_ab[q], prob.r, f"R_ab[{q}]", self.device)
         parr = (Problem * n)(*probs)
         ra = (ctypes.c_void_p * n)(*[t.data_ptr() for t in R_aa])
         rb = (ctypes.c_void_p * n)(*[t.data_ptr() for t in R_ab])
@@ -401,6 +479,8 @@ class Context:
         return list(n2) if want_norm else None
 
     def autotune_batched_raw(self, probs, opts):
+        for prob in probs:
+            _check_opts(opts, prob.r)
         n = len(probs)
         parr = (Problem * n)(*probs)
         best = ctypes.c_int32(-1)
@@ -427,6 +507,9 @@ class Context:
         return [(o[0], o[1], v) for o, v in zip(outs, n2)]
 
     def energy_vjp_raw(self, prob, Ebar, h_bar, V_bar, d2aa_bar, d2ab_bar):
+        for name, t in (("V_bar", V_bar), ("d2aa_bar", d2aa_bar), ("d2ab_bar", d2ab_bar)):
+            _check_dev4(t, prob.r, name, self.device)
+        _check_dev2(h_bar, prob.r, "h_bar", self.device)
         self._check(_lib.acse_energy_vjp(self._h, ctypes.byref(prob), float(Ebar), _ptr(h_bar),
                                          _ptr(V_bar), _ptr(d2aa_bar), _ptr(d2ab_bar)))
 
@@ -485,6 +568,39 @@ class ACSEEnergy(torch.autograd.Function):
         h, V, d2aa, d2ab = fctx.saved_tensors
         g = ctx.energy_vjp(h, V, d2aa, d2ab, n_alpha, float(Eb))
         return (None,) + tuple(x.to(t.dtype) for x, t in zip(g, (h, V, d2aa, d2ab))) + (None,)
+
+
+# Options of ``Context.solve`` that change the iteration a checkpoint continues,
+# with their defaults there.
+_SOLVE_TAG_DEFAULTS = dict(de_tol=1e-6, control="fixed", max_halvings=8, eps_max=0.0, precision="fp64",
+                           active=None, sigma=None)
+
+
+def checkpoint_tag(h, V, n_alpha, **kw):
+    """Hash naming the problem and the iteration of a ``solve_checkpointed`` file:
+    h, V, n_alpha, the reconstruction (``sigma``), the precision of the
+    contractions, the active mask, the step control, max_halvings, eps_max and
+    de_tol (defaults as in ``Context.solve``).  The first step size is not part
+    of it: a resumed run continues with the step size the file holds."""
+    import hashlib
+    import numpy as np
+
+    tag = hashlib.sha256()
+    for x in (h, V):
+        tag.update(np.ascontiguousarray(_host64(x)).tobytes())
+    tag.update(str(int(n_alpha)).encode())
+    opt = {k: kw.get(k, d) for k, d in _SOLVE_TAG_DEFAULTS.items()}
+    sigma = opt["sigma"]
+    if sigma is not None and sigma is not False:
+        tag.update(b"NY:" + (b"default" if sigma is True else bytes(str([int(x) for x in sigma]), "ascii")))
+    control = opt["control"]
+    control = CONTROLS[control] if isinstance(control, str) else int(control)
+    precision = opt["precision"]
+    precision = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
+    active = None if opt["active"] is None else [bool(a) for a in opt["active"]]
+    tag.update(repr((precision, active, control, int(opt["max_halvings"]), float(opt["eps_max"]).hex(),
+                     float(opt["de_tol"]).hex())).encode())
+    return tag.hexdigest()
 
 
 def _host64(x):

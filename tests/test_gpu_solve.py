@@ -207,3 +207,9 @@ def test_solve_checkpoint_resume(acse, ctx, tmp_path):
         ctx.solve_checkpointed(p["h"] * 1.01, *args[1:], path=path, every=1, max_iter=6, eps=1e-3)
     with pytest.raises(ValueError, match="another problem"):
         ctx.solve_checkpointed(*args, path=path, every=1, max_iter=6, eps=1e-3, sigma=True)
+    # ... and so is a resume with options that change the iteration
+    for kw in (dict(precision="fp32"), dict(control="backtrack"), dict(de_tol=1e-8),
+               dict(active=[True] * 3 + [False] * 3), dict(max_halvings=2)):
+        with pytest.raises(ValueError, match="another problem"):
+            ctx.solve_checkpointed(*args, path=path, every=1, max_iter=6, eps=1e-3,
+                                   **dict(dict(de_tol=0.0), **kw))

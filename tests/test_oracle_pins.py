@@ -262,16 +262,141 @@ def test_orbital_rotation_covariance():
     assert abs(n2 - n22) < 1e-10 * n2
 
 
-def test_active_mask_zeroes_all_active_elements():
+def _mask_pin_holds(mask_fn):
+    """The active-mask rule (all four spatial indices active -> zeroed, in every
+    spin block) on r = 5 with orbitals 1, 2, 3 active, checked against hand-picked
+    spin-orbital elements and against a keep/zero table built with explicit index
+    loops.  Returns True iff ``mask_fn(active, r)`` (True = kept) satisfies both."""
+    r = 5
+    active = [False, True, True, True, False]
+    m = np.asarray(mask_fn(np.array(active), r), dtype=bool)
+    if m.shape != (2 * r,) * 4:
+        return False
+    a, b = 0, r   # offsets of the alpha and beta spin orbitals
+    zeroed = [(1 + a, 2 + a, 3 + a, 1 + a),          # alpha-alpha block
+              (1 + b, 2 + b, 3 + b, 1 + b),          # beta-beta block
+              (1 + a, 2 + b, 3 + a, 1 + b),          # (alpha beta | alpha beta)
+              (1 + a, 2 + b, 3 + b, 1 + a),          # (alpha beta | beta alpha)
+              (3 + b, 3 + a, 2 + b, 2 + a)]
+    kept = [(0 + a, 2 + a, 3 + a, 1 + a), (1 + a, 2 + a, 3 + a, 4 + a),
+            (0 + a, 2 + b, 3 + a, 1 + b), (1 + b, 2 + b, 3 + b, 4 + b),
+            (1 + a, 4 + b, 3 + b, 1 + a), (0 + a, 0 + b, 0 + a, 0 + b)]
+    if any(m[t] for t in zeroed) or not all(m[t] for t in kept):
+        return False
+    n = 2 * r
+    for p in range(n):
+        for q in range(n):
+            for u in range(n):
+                for v in range(n):
+                    all_active = (active[p % r] and active[q % r] and active[u % r]
+                                  and active[v % r])
+                    if m[p, q, u, v] != (not all_active):
+                        return False
+    return True
+
+
+def test_active_mask_pin():
+    """C-9 (the method section's all-active option): the oracle's mask passes
+    the pin; a rule that zeroes an element when ANY index is active, an
+    inverted rule, and one that ignores the beta spin orbitals each fail it."""
+    assert _mask_pin_holds(st.active_mask)
+
+    def any_rule(active, r):
+        so = np.concatenate([active, active])
+        return ~(so[:, None, None, None] | so[None, :, None, None] | so[None, None, :, None]
+                 | so[None, None, None, :])
+
+    def inverted(active, r):
+        return ~st.active_mask(active, r)
+
+    def alpha_only(active, r):
+        so = np.concatenate([active, np.zeros_like(active)])
+        return ~(so[:, None, None, None] & so[None, :, None, None] & so[None, None, :, None]
+                 & so[None, None, None, :])
+
+    for wrong in (any_rule, inverted, alpha_only):
+        assert not _mask_pin_holds(wrong), wrong.__name__
+
+
+def test_active_mask_in_the_step():
+    """The step zeroes exactly the all-active elements of R before the update
+    map, keeps the rest unchanged, and takes the norm before masking."""
     p = gen.problem(5, 4, 8, seed=2)
     active = np.array([0, 1, 1, 1, 0], dtype=bool)
     o = st.step(p["h"], p["V"], p["N"], p["gamma"], p["d2aa"], p["d2ab"], 1e-3, active=active,
                 keep_spin_orbital=True)
-    mask = st.active_mask(active, 5)
-    assert np.all(o["Rm"][~mask] == 0.0)
-    assert np.all(o["Rm"][mask] == o["R"][mask])
+    n = 10
+    for idx in np.ndindex(n, n, n, n):
+        if all(active[x % 5] for x in idx):
+            assert o["Rm"][idx] == 0.0
+        else:
+            assert o["Rm"][idx] == o["R"][idx]
+    assert np.abs(o["R"][1, 2, 3, 1]) > 0.0    # the zeroed element was not zero already
     assert abs(o["norm2"] - np.sum(o["R"] ** 2)) < 1e-12 * o["norm2"]   # norm before masking
     assert abs(np.sum(o["K"] * o["U"]) + np.sum(o["Rm"] * o["R"])) < 1e-10 * o["norm2"]
+
+
+def _explicit_traces(d2aa, d2ab):
+    r = d2aa.shape[0]
+    taa = tab = 0.0
+    for p in range(r):
+        for q in range(r):
+            taa += d2aa[p, q, p, q]
+            tab += d2ab[p, q, p, q]
+    return taa, tab
+
+
+def _restoration_pin_holds(fn):
+    """Trace restoration (C-10, App. A traces) on blocks carrying a planted
+    drift, different in the two blocks: the output traces must equal the input
+    ones (hand-summed), and each output block must be its drifted input times
+    one positive number (the restoration changes nothing but the scale)."""
+    p = gen.problem(5, 4, 10, seed=3)
+    t0 = _explicit_traces(p["d2aa"], p["d2ab"])
+    rng = np.random.default_rng(7)
+    drift_aa = 1.07 * p["d2aa"] + 1e-3 * rng.standard_normal(p["d2aa"].shape)
+    drift_ab = 0.93 * p["d2ab"] + 1e-3 * rng.standard_normal(p["d2ab"].shape)
+    out_aa, out_ab, _ = fn(drift_aa, drift_ab, t0)
+    t1 = _explicit_traces(out_aa, out_ab)
+    if abs(t1[0] - t0[0]) > 1e-13 * abs(t0[0]) or abs(t1[1] - t0[1]) > 1e-13 * abs(t0[1]):
+        return False
+    for out, drift in ((out_aa, drift_aa), (out_ab, drift_ab)):
+        c = float(np.sum(out * drift) / np.sum(drift * drift))
+        if not c > 0 or np.abs(out - c * drift).max() > 1e-14 * np.abs(out).max():
+            return False
+    return True
+
+
+def test_trace_restoration_pin():
+    """The oracle's restoration passes; an inverted ratio, one factor for the
+    whole 2-RDM, and no restoration at all each fail."""
+    assert _restoration_pin_holds(st.restore_traces)
+
+    def inverted(aa, ab, t0):
+        t1 = _explicit_traces(aa, ab)
+        return aa * (t1[0] / t0[0]), ab * (t1[1] / t0[1]), None
+
+    def whole(aa, ab, t0):
+        t1 = _explicit_traces(aa, ab)
+        s = (t0[0] + t0[1]) / (t1[0] + t1[1])
+        return aa * s, ab * s, None
+
+    def none(aa, ab, t0):
+        return aa, ab, None
+
+    for wrong in (inverted, whole, none):
+        assert not _restoration_pin_holds(wrong), wrong.__name__
+
+
+def test_step_keeps_app_a_traces():
+    """After a step the blocks keep the App. A traces of the input state
+    (N_a(N_a-1)/2 and N_a N_b/2 for the FCI singlet's 2-RDM)."""
+    rng = np.random.default_rng(0)
+    h, V = gen.hamiltonian(rng, 4, 6)
+    p = fm.fci_singlet_problem(h, V, 4)
+    o = st.step(h, V, 4, p["gamma"], p["d2aa"], p["d2ab"], 1e-2)
+    taa, tab = _explicit_traces(o["d2aa"], o["d2ab"])
+    assert abs(taa - 1.0) < 1e-13 and abs(tab - 2.0) < 1e-13
 
 
 # --------------------------------------------------------------------------
