@@ -218,7 +218,13 @@ def test_vjp_argument_errors(acse, ctx):
     prob, keep = ctx.problem(p["h"], p["V"], p["gamma"], p["d2aa"], p["d2ab"], p["N"] // 2)
     opts = ctx.options("fp64")
     out = [torch.empty_like(t) for t in keep]
-    with pytest.raises(acse.AcseError):
+    # the binding refuses a missing cotangent before the library sees it ...
+    with pytest.raises(ValueError, match="Rbar_aa"):
         ctx.residual_vjp_raw(prob, opts, None, keep[3], *out)
+    # ... and the library itself reports a NULL one
+    import ctypes
+    st = acse._lib.acse_residual_vjp(ctx._h, ctypes.byref(prob), ctypes.byref(opts), None,
+                                     acse._ptr(keep[3]), *[acse._ptr(t) for t in out])
+    assert st == 1   # ACSE_ERR_ARG
     with pytest.raises(acse.AcseError):
         ctx.energy_vjp_raw(prob, float("nan"), out[0], out[1], out[3], out[4])
