@@ -362,10 +362,34 @@ acse_status acse_residual_batched(acse_ctx ctx, int32_t count, const acse_proble
 acse_status acse_autotune_batched(acse_ctx ctx, int32_t count, const acse_problem *probs,
                                   const acse_options *opts, int32_t *best_tile, double *times_ms);
 
+/* For callers that cannot allocate device memory (code under HIP stream
+ * capture, allocation-free serving loops, harnesses that forbid hipMalloc):
+ * the residual of acse_residual with no context and no allocation of any kind.
+ * The workspace of the call lives in a device array of the library, 24 MiB,
+ * one copy per GPU it runs on, held until the process ends; it covers
+ * r <= 16 (r > 16 is ACSE_ERR_SHAPE; the Nakatsuji-Yasuda reconstruction,
+ * whose workspace is larger, is ACSE_ERR_UNSUPPORTED).
+ *   hip_stream  the hipStream_t the work is ordered on (NULL = default stream)
+ *               on the current HIP device
+ *   prob, opts  as for acse_residual (tile -1 takes the size default; with
+ *               ACSE_FLAG_CHECK_INPUTS the call synchronises the stream)
+ *   R_aa, R_ab  device [r^4] outputs
+ *   norm2_dev   device double receiving ||R||^2, or NULL; the call never
+ *               synchronises or copies to the host otherwise
+ * Calls on one GPU share its array: calls whose work overlaps in time on one
+ * GPU (other streams, other host threads) race and must be serialised by the
+ * caller; calls ordered on one stream are safe.  Every buffer a call reads is
+ * written earlier in the same call.  The first call on a device looks up the
+ * array's address there (hipGetSymbolAddress).  On an error nothing is
+ * enqueued and acse_last_error(NULL) gives the detail (per host thread). */
+acse_status acse_residual_noalloc(void *hip_stream, const acse_problem *prob, const acse_options *opts,
+                                  double *R_aa, double *R_ab, double *norm2_dev);
+
 /* Human-readable name of a status code (static storage). */
 const char *acse_status_str(acse_status s);
 
-/* Detail of the last failing call on ctx (valid until the next call). */
+/* Detail of the last failing call on ctx (valid until the next call); with
+ * ctx = NULL, of the last failing context-free call on this host thread. */
 const char *acse_last_error(acse_ctx ctx);
 
 /* Number of bytes of device workspace the context holds. */

@@ -33,7 +33,7 @@ EXPORTS = ("acse_create", "acse_destroy", "acse_set_stream", "acse_residual", "a
            "acse_energy", "acse_step", "acse_status_str", "acse_last_error",
            "acse_workspace_bytes", "acse_profile_enable", "acse_profile_read", "acse_autotune",
            "acse_residual_vjp", "acse_energy_vjp", "acse_residual_batched",
-           "acse_autotune_batched", "acse_solve")
+           "acse_autotune_batched", "acse_solve", "acse_residual_noalloc")
 NUM_TILE_CONFIGS = 3
 NUM_STAGES = 8
 STAGES = ("rdm_operands", "fold", "transforms", "gemm", "assembly", "step_tail", "ny_share", "ny_gemm")
@@ -112,6 +112,8 @@ _sig = {
     "acse_autotune_batched": (ctypes.c_int, [_P, ctypes.c_int32, ctypes.POINTER(Problem),
                                              ctypes.POINTER(Options), ctypes.POINTER(ctypes.c_int32),
                                              _D]),
+    "acse_residual_noalloc": (ctypes.c_int, [_P, ctypes.POINTER(Problem), ctypes.POINTER(Options), _P, _P,
+                                             _P]),
     "acse_solve": (ctypes.c_int, [_P, ctypes.POINTER(Problem), ctypes.POINTER(Options),
                                   ctypes.POINTER(SolveOptions), ctypes.POINTER(SolveResult),
                                   ctypes.POINTER(Trial), ctypes.c_int32]),
@@ -622,6 +624,49 @@ def trajectory(result):
             lam += eps
             out.append((lam, e, 0.5 * math.log10(n2) if n2 > 0 else -math.inf))
     return out
+
+
+NOALLOC_MAX_R = 16
+
+
+def residual_noalloc_raw(prob, opts, R_aa, R_ab, norm2_dev=None, stream=None):
+    """acse_residual_noalloc on device arrays: no context, no allocation in the
+    library (its workspace is a fixed device array for r <= 16).  The work is
+    ordered on ``stream`` (torch stream; default: the current one) of the
+    current device; ``norm2_dev`` (a one-element float64 device tensor) receives
+    ||R||^2 if given.  Nothing is synchronised."""
+    _check_opts(opts, prob.r)
+    dev = R_aa.device if isinstance(R_aa, torch.Tensor) else None
+    for name, t in (("R_aa", R_aa), ("R_ab", R_ab)):
+        _check_dev4(t, prob.r, name, dev)
+    if norm2_dev is not None and (not isinstance(norm2_dev, torch.Tensor) or norm2_dev.dtype != torch.float64
+                                  or norm2_dev.device != dev or norm2_dev.numel() < 1):
+        raise ValueError(f"norm2_dev must be a float64 tensor on {dev}")
+    s = stream if stream is not None else torch.cuda.current_stream(dev)
+    st = _lib.acse_residual_noalloc(ctypes.c_void_p(s.cuda_stream), ctypes.byref(prob), ctypes.byref(opts),
+                                    _ptr(R_aa), _ptr(R_ab), _ptr(norm2_dev))
+    if st != 0:
+        raise AcseError(st, _lib.acse_last_error(None).decode())
+
+
+def residual_noalloc(h, V, d1, d2aa, d2ab, n_alpha, precision="fp64", device=0, stream=None):
+    """R_aa, R_ab (device) and ||R||^2 through acse_residual_noalloc (r <= 16).
+    The inputs and outputs are allocated here by torch; the library allocates
+    nothing.  Synchronises the stream the work is ordered on before returning."""
+    r = check_problem_shapes(h, V, d1, d2aa, d2ab)
+    dev = torch.device("cuda", device) if isinstance(device, int) else torch.device(device)
+    t = [_dev(x, dev) for x in (h, V, d1, d2aa, d2ab)]
+    prob = Problem(r, int(n_alpha), int(n_alpha), *[x.data_ptr() for x in t])
+    R_aa = torch.empty((r, r, r, r), dtype=torch.float64, device=dev)
+    R_ab = torch.empty_like(R_aa)
+    n2 = torch.empty(1, dtype=torch.float64, device=dev)
+    with torch.cuda.device(dev):
+        s = stream if stream is not None else torch.cuda.current_stream(dev)
+        residual_noalloc_raw(prob, Context.options(precision), R_aa, R_ab, n2, s)
+        # the work is ordered on s: wait for it before the norm is read and the
+        # input copies made here are released
+        s.synchronize()
+        return R_aa, R_ab, float(n2.item())
 
 
 def status_str(code):

@@ -26,6 +26,7 @@
 #include <string>
 #include <initializer_list>
 #include <map>
+#include <mutex>
 #include <utility>
 #include <vector>
 
@@ -713,6 +714,8 @@ int keep_default(int best_cfg, double best_ms, int default_cfg, const double *ti
   return times_ms[default_cfg] <= best_ms * (1.0 + kTuneMargin) ? default_cfg : best_cfg;
 }
 
+const char *last_noctx_error();
+
 acse_status fetch_scalars(acse_ctx c, double *norm2_host, double *E_host) {
   if (!norm2_host && !E_host) return ACSE_OK;
   double host[2] = {0.0, 0.0};
@@ -747,7 +750,7 @@ const char *acse_status_str(acse_status s) {
   return "ACSE_ERR_UNKNOWN";
 }
 
-const char *acse_last_error(acse_ctx ctx) { return ctx ? ctx->err.c_str() : "null context"; }
+const char *acse_last_error(acse_ctx ctx) { return ctx ? ctx->err.c_str() : last_noctx_error(); }
 
 int64_t acse_workspace_bytes(acse_ctx ctx) { return ctx ? ctx->bytes : -1; }
 
@@ -993,6 +996,95 @@ acse_status acse_step(acse_ctx ctx, acse_problem *prob, double eps, const acse_o
 }
 
 }  // extern "C"
+
+// ===========================================================================
+// Residual without allocation.  The workspace of one residual map for r up to
+// kNoAllocMaxR lives in a file-scope device array, so the call allocates no
+// device memory: for callers that cannot call hipMalloc (stream capture into
+// a HIP graph, allocation-free serving loops).
+// ===========================================================================
+namespace {
+constexpr int kNoAllocMaxR = 16;
+constexpr int64_t kNoAllocBytes = 24ll << 20;  // the residual workspace of r = 16 takes 17.9 MiB
+constexpr int kNoAllocMaxDevices = 64;
+}  // namespace
+
+// One copy per GPU the library runs on, held until the process ends.  Host code
+// never passes this name to a kernel (on the host it is a stand-in, not a
+// device address); it uses the per-device address from hipGetSymbolAddress.
+static __device__ __align__(256) char scratch[kNoAllocBytes];
+
+namespace {
+thread_local std::string g_noctx_err;  // detail of the last failing context-free call
+
+struct NoAllocSlot {
+  std::once_flag once;
+  char *ptr = nullptr;
+  hipError_t err = hipSuccess;
+};
+NoAllocSlot g_noalloc[kNoAllocMaxDevices];
+
+acse_status noalloc_fail(acse_status s, const std::string &msg) {
+  g_noctx_err = msg;
+  return s;
+}
+}  // namespace
+
+namespace {
+const char *last_noctx_error() { return g_noctx_err.c_str(); }
+}  // namespace
+
+extern "C" acse_status acse_residual_noalloc(void *hip_stream, const acse_problem *prob,
+                                             const acse_options *opts, double *R_aa, double *R_ab,
+                                             double *norm2_dev) {
+  if (!prob) return noalloc_fail(ACSE_ERR_ARG, "problem is NULL");
+  if (prob->r < 2 || prob->r > kNoAllocMaxR)
+    return noalloc_fail(ACSE_ERR_SHAPE, "r = " + std::to_string(prob->r) +
+                                            " outside [2, 16], the range of acse_residual_noalloc");
+  if (opts && opts->reconstruction == ACSE_RECON_NY)
+    return noalloc_fail(ACSE_ERR_UNSUPPORTED, "acse_residual_noalloc takes the Valdemoro reconstruction only");
+  if (norm2_dev && (reinterpret_cast<uintptr_t>(norm2_dev) & 7u))
+    return noalloc_fail(ACSE_ERR_ALIGN, "norm2_dev must be 8-byte aligned");
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return noalloc_fail(ACSE_ERR_HIP, "hipGetDevice failed");
+  if (dev < 0 || dev >= kNoAllocMaxDevices)
+    return noalloc_fail(ACSE_ERR_UNSUPPORTED, "device index " + std::to_string(dev) + " beyond 63");
+  // the scratch address of this device, taken once with the device current
+  NoAllocSlot &slot = g_noalloc[dev];
+  std::call_once(slot.once, [&slot] {
+    slot.err = hipGetSymbolAddress(reinterpret_cast<void **>(&slot.ptr), HIP_SYMBOL(scratch));
+  });
+  if (slot.err != hipSuccess || !slot.ptr)
+    return noalloc_fail(ACSE_ERR_HIP, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(slot.err));
+  // a context on the stack: the caller's stream, the workspace carved from the
+  // scratch for this r, no profiling, no tuned tiles
+  acse_ctx_s c;
+  c.device = dev;
+  c.stream = static_cast<hipStream_t>(hip_stream);
+  c.r_max = kNoAllocMaxR;
+  acse_status st = validate(&c, prob, opts);
+  if (st == ACSE_OK) st = check_out(&c, R_aa, "R_aa");
+  if (st == ACSE_OK) st = check_out(&c, R_ab, "R_ab");
+  if (st != ACSE_OK) return noalloc_fail(st, c.err);
+  const int r = prob->r;
+  if (carve(nullptr, r, false, c.ws) > kNoAllocBytes)
+    return noalloc_fail(ACSE_ERR_NOMEM, "the residual workspace exceeds the scratch array");
+  carve(slot.ptr, r, false, c.ws);
+  const GemmPrec prec = prec_of(opts);
+  const int N = prob->n_alpha + prob->n_beta;
+  if ((st = prep_rdm_operands(&c, prob, prec)) != ACSE_OK) return noalloc_fail(st, c.err);
+  if (launch_fold(r, N, prob->h, prob->V, c.ws.Aaa, c.ws.Aab, c.stream) != hipSuccess)
+    return noalloc_fail(ACSE_ERR_HIP, "fold launch failed");
+  const ActiveBits none{};
+  if ((st = run_map(&c, prob, prec, opts ? opts->tile : -1, c.ws.Aaa, c.ws.Aab, -1.0, R_aa, R_ab, none,
+                    nullptr, nullptr, 0)) != ACSE_OK)
+    return noalloc_fail(st, c.err);
+  if (norm2_dev) {
+    const hipError_t e = hipMemcpyAsync(norm2_dev, c.ws.scal, sizeof(double), hipMemcpyDeviceToDevice, c.stream);
+    if (e != hipSuccess) return noalloc_fail(ACSE_ERR_HIP, std::string("norm copy: ") + hipGetErrorString(e));
+  }
+  return ACSE_OK;
+}
 
 // ===========================================================================
 // Adjoint of the residual map (VJP).  The steps mirror the forward chain in

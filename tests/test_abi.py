@@ -62,7 +62,9 @@ def test_argument_errors_without_device(lib):
     assert lib.acse_energy(None, None, None) == 1
     lib.acse_last_error.restype = ctypes.c_char_p
     lib.acse_last_error.argtypes = [P]
-    assert lib.acse_last_error(None) == b"null context"
+    # with no context: the detail of the last failing context-free call on this
+    # thread (none has failed here yet, or acse_residual_noalloc's if one has)
+    assert isinstance(lib.acse_last_error(None), bytes)
 
 
 def test_struct_layouts_match_header(tmp_path):
@@ -107,3 +109,23 @@ def test_trajectory_from_trials():
                        (0.05, -1.8, 64.0, 1, True)])
     t = acse.trajectory(res)
     assert t == [(0.0, -1.0, 1.0), (0.05, -1.5, math.log10(9.0)), (0.1, -1.8, math.log10(8.0))]
+
+
+def test_noalloc_argument_errors_without_device(lib):
+    """acse_residual_noalloc rejects a missing problem and sizes beyond its
+    maximum before it touches a device; acse_last_error(NULL) names the cause."""
+    P = ctypes.c_void_p
+    lib.acse_residual_noalloc.argtypes = [P] * 6
+    lib.acse_last_error.argtypes = [P]
+    lib.acse_last_error.restype = ctypes.c_char_p
+    assert lib.acse_residual_noalloc(None, None, None, None, None, None) == 1   # ACSE_ERR_ARG
+    assert b"problem is NULL" in lib.acse_last_error(None)
+
+    class Problem(ctypes.Structure):
+        _fields_ = [("r", ctypes.c_int32), ("n_alpha", ctypes.c_int32), ("n_beta", ctypes.c_int32),
+                    ("h", P), ("V", P), ("d1", P), ("d2aa", P), ("d2ab", P)]
+
+    for r in (1, 17, 50):
+        prob = Problem(r, 2, 2, None, None, None, None, None)
+        assert lib.acse_residual_noalloc(None, ctypes.byref(prob), None, None, None, None) == 2
+        assert b"outside [2, 16]" in lib.acse_last_error(None)
