@@ -29,7 +29,8 @@ import numpy as np
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-PEAK_TFLOPS = {"fp64": 78.6, "fp32": 157.3, "bf16x3": 2516.6}
+PEAK_TFLOPS = {"fp64": 78.6, "fp32": 157.3, "bf16x3": 2516.6, "int8crt": 5000.0}  # int8: dense TOP/s
+CRT_MODULI = 13  # modulus count of the int8crt mode (the library default)
 GOLDEN = os.path.join(ROOT, "tests", "golden", "r50_step.json")
 TRAFFIC = os.path.join(ROOT, "profiles", "gemm_traffic_r50.json")
 # the GEMM kernel and the host code that sets up its launches (operand layout, K extent)
@@ -78,6 +79,8 @@ TRAITS = {"fp64": "TrF64", "fp32": "TrF32", "bf16x3": "TrBF16x3"}
 
 
 def gemm_kernel_name(prec, cfg):
+    if prec == "int8crt":
+        return "acse::(anonymous namespace)::gemm_crt_kernel"
     bm, bn, bk, ns = TILE_SHAPES[prec][cfg]
     wpe = 2 if prec == "fp64" and bm * bn >= 128 * 128 else 1   # register cap of the instantiation
     return f"acse::gemm_nt_kernel<acse::{TRAITS[prec]}, {bm}, {bn}, {bk}, {ns}, {wpe}>"
@@ -445,11 +448,15 @@ def main():
                 err[f"{k}_sample_rel"] = float(np.abs(val - ref).max() / np.abs(ref).max())
                 err[f"{k}_norm_rel"] = abs(float(np.linalg.norm(got[k])) - golden["norms"][k]) / golden["norms"][k]
         gemm_avg = gemm_ms / max(gemm_n, 1)
-        achieved = gemm_flops(r) / (gemm_avg * 1e-3) / 1e12
+        # executed work of the dominant launch: int8 ops (one product per modulus) for
+        # int8crt, floating-point operations otherwise
+        gemm_work = gemm_flops(r) * (CRT_MODULI if mode == "int8crt" else 1)
+        achieved = gemm_work / (gemm_avg * 1e-3) / 1e12
         results[mode] = dict(
             ms_per_step=ms, steps_per_s=1e3 / ms, wall_s=wall, residual_ms=res_ms,
             residual_evals_per_s=1e3 / res_ms,
             gemm_avg_ms=gemm_avg, gemm_launches=gemm_n, gemm_tflops=achieved,
+            gemm_fp64_equivalent_tflops=gemm_flops(r) / (gemm_avg * 1e-3) / 1e12,
             stage_ms_per_step={k: v[0] / args.steps for k, v in prof.items()},
             useful_tflops_step=2 * gemm_flops(r) / (ms * 1e-3) / 1e12,
             error_vs_oracle=err, energy1=E1, norm2=n2,
@@ -475,7 +482,7 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": {"fp64": "f64", "fp32": "f32", "bf16x3": "bf16x3"}[head],
+        "dtype": {"fp64": "f64", "fp32": "f32", "bf16x3": "bf16x3", "int8crt": "i8 (CRT, FP64 result)"}[head],
         "data": "synthetic",
         "config": {"workload": f"{args.workload}: r={r} spatial orbitals, N={N}, singlet "
                                "alpha-alpha/alpha-beta blocks, one acse_step (eps=1e-3) per step",

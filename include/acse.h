@@ -82,7 +82,23 @@ typedef enum {
 typedef enum {
   ACSE_FP64 = 0,   /* FP64 MFMA (v_mfma_f64_16x16x4) */
   ACSE_FP32 = 1,   /* FP32 operands, FP32 MFMA accumulation */
-  ACSE_BF16X3 = 2  /* split-BF16 products a_hi b_hi + a_hi b_lo + a_lo b_hi, FP32 accumulation */
+  ACSE_BF16X3 = 2, /* split-BF16 products a_hi b_hi + a_hi b_lo + a_lo b_hi, FP32 accumulation */
+  ACSE_INT8CRT = 3 /* exact accumulation on the int8 MFMA: each operand row is scaled by a
+                      power of two to integers of k bits (the largest k with
+                      K 2^(2k) < M/4; k = 44 for 13 moduli at K = 2500), the integers are
+                      split into their residues modulo `moduli` pairwise coprime moduli
+                      <= 256, each modulus runs one int8 product with exact int32
+                      accumulation (v_mfma_i32_16x16x64_i8), and the exact integer
+                      product is rebuilt by the Chinese remainder theorem in FP64.  The
+                      only rounding is that of the operands to k bits relative to their
+                      row's largest magnitude.  Residual, update map, step, autotune
+                      and the Euler iteration (fixed and backtracking controls); the
+                      adjoint, the quadratic control, the batched residual, the NY
+                      reconstruction and acse_residual_noalloc are
+                      ACSE_ERR_UNSUPPORTED with it.  The first call allocates residue
+                      buffers for r_max: 12 x (15 x op_rows x round_up(r_max^2, 128) +
+                      4 op_rows) bytes, op_rows = r_max^2 rounded up to 256 (1.2 GB at
+                      r_max = 50). */
 } acse_precision;
 
 typedef struct {
@@ -110,6 +126,10 @@ typedef struct {
                              in the Hartree-Fock reference, -1 for an unoccupied one;
                              NULL = orbitals 0 .. n_alpha-1 occupied.  Other values are an
                              ACSE_ERR_ARG. */
+  int32_t moduli;         /* ACSE_INT8CRT: number of moduli, 8..15 (0 = 13); more moduli
+                             give more bits k per operand (k = 40 / 44 / 48 at
+                             K = 2500 for 12 / 13 / 14) and one more int8 product
+                             each.  Ignored by the other precisions (0 or 8..15). */
 } acse_options;
 
 /* 3-RDM reconstruction of the residual map (Eq. (7)).

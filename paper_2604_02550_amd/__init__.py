@@ -22,8 +22,8 @@ if not os.path.exists(LIB_PATH):
                       "(or __graft_entry__.build())")
 _lib = ctypes.CDLL(LIB_PATH)
 
-FP64, FP32, BF16X3 = 0, 1, 2
-PRECISIONS = {"fp64": FP64, "fp32": FP32, "bf16x3": BF16X3}
+FP64, FP32, BF16X3, INT8CRT = 0, 1, 2, 3
+PRECISIONS = {"fp64": FP64, "fp32": FP32, "bf16x3": BF16X3, "int8crt": INT8CRT}
 STATUS = {0: "ACSE_OK", 1: "ACSE_ERR_ARG", 2: "ACSE_ERR_SHAPE", 3: "ACSE_ERR_ALIGN",
           4: "ACSE_ERR_UNSUPPORTED", 5: "ACSE_ERR_NOMEM", 6: "ACSE_ERR_HIP",
           7: "ACSE_ERR_NONFINITE"}
@@ -51,7 +51,8 @@ class ProfileData(ctypes.Structure):
 
 class Options(ctypes.Structure):
     _fields_ = [("precision", ctypes.c_int32), ("active", ctypes.c_void_p), ("tile", ctypes.c_int32),
-                ("flags", ctypes.c_int32), ("reconstruction", ctypes.c_int32), ("ny_sigma", ctypes.c_void_p)]
+                ("flags", ctypes.c_int32), ("reconstruction", ctypes.c_int32), ("ny_sigma", ctypes.c_void_p),
+                ("moduli", ctypes.c_int32)]
 
 
 RECON_V, RECON_NY = 0, 1
@@ -258,10 +259,11 @@ class Context:
         return prob, t
 
     @staticmethod
-    def options(precision="fp64", active=None, tile=-1, flags=0, sigma=None):
+    def options(precision="fp64", active=None, tile=-1, flags=0, sigma=None, moduli=0):
         """acse_options.  ``sigma`` selects the Nakatsuji-Yasuda reconstruction:
         True for the default reference occupations (orbitals below n_alpha
-        occupied) or a per-orbital sequence of +1 / -1; None is Valdemoro."""
+        occupied) or a per-orbital sequence of +1 / -1; None is Valdemoro.
+        ``moduli``: modulus count of the "int8crt" precision (0 = 13)."""
         prec = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
         keep = None
         act = None
@@ -274,7 +276,7 @@ class Context:
             if sigma is not True:
                 keep_sig = (ctypes.c_int8 * len(sigma))(*[int(x) for x in sigma])
                 sig = ctypes.cast(keep_sig, ctypes.c_void_p)
-        o = Options(prec, act, int(tile), int(flags), recon, sig)
+        o = Options(prec, act, int(tile), int(flags), recon, sig, int(moduli))
         o._keep = (keep, keep_sig)
         o._lens = {"active": None if keep is None else len(keep),
                    "ny_sigma": None if keep_sig is None else len(keep_sig)}
@@ -289,17 +291,18 @@ class Context:
                                        _ptr(R_ab), ctypes.byref(n2) if want_norm else None))
         return n2.value
 
-    def residual(self, h, V, d1, d2aa, d2ab, n_alpha, precision="fp64", tile=-1, flags=0, sigma=None):
+    def residual(self, h, V, d1, d2aa, d2ab, n_alpha, precision="fp64", tile=-1, flags=0, sigma=None,
+                 moduli=0):
         """R_aa, R_ab (device, float64) and ||R||^2 of Eq. (4)."""
         prob, keep = self.problem(h, V, d1, d2aa, d2ab, n_alpha)
         r = prob.r
         R_aa = torch.empty((r, r, r, r), dtype=torch.float64, device=self.device)
         R_ab = torch.empty_like(R_aa)
-        n2 = self.residual_raw(prob, self.options(precision, None, tile, flags, sigma), R_aa, R_ab)
+        n2 = self.residual_raw(prob, self.options(precision, None, tile, flags, sigma, moduli), R_aa, R_ab)
         return R_aa, R_ab, n2
 
     def update_map(self, h, V, d1, d2aa, d2ab, n_alpha, X_aa, X_ab, precision="fp64", tile=-1, flags=0,
-                   sigma=None):
+                   sigma=None, moduli=0):
         """U = 1/2 <[a+a+aa, sum X a+a+aa]> for anti-Hermitian X (Eq. (9))."""
         prob, keep = self.problem(h, V, d1, d2aa, d2ab, n_alpha)
         for name, x in (("X_aa", X_aa), ("X_ab", X_ab)):
@@ -309,7 +312,7 @@ class Context:
         U_aa = torch.empty_like(X_aa)
         U_ab = torch.empty_like(X_ab)
         self._check(_lib.acse_update_map(self._h, ctypes.byref(prob),
-                                         ctypes.byref(self.options(precision, None, tile, flags, sigma)),
+                                         ctypes.byref(self.options(precision, None, tile, flags, sigma, moduli)),
                                          _ptr(X_aa), _ptr(X_ab), _ptr(U_aa), _ptr(U_ab)))
         return U_aa, U_ab
 
@@ -338,7 +341,7 @@ class Context:
         return e.value, n2.value
 
     def step(self, h, V, d1, d2aa, d2ab, n_alpha, eps=1e-3, precision="fp64", active=None,
-             tile=-1, return_ru=False, flags=0, sigma=None):
+             tile=-1, return_ru=False, flags=0, sigma=None, moduli=0):
         """One Euler step of Eq. (9) on device copies; returns a dict with the new
         d1, d2aa, d2ab, the energy after the step and ||R||^2 before it."""
         prob, t = self.problem(h, V, d1, d2aa, d2ab, n_alpha)
@@ -347,7 +350,7 @@ class Context:
         bufs = [None] * 4
         if return_ru:
             bufs = [torch.empty((r, r, r, r), dtype=torch.float64, device=self.device) for _ in range(4)]
-        E, n2 = self.step_raw(prob, eps, self.options(precision, active, tile, flags, sigma), *bufs)
+        E, n2 = self.step_raw(prob, eps, self.options(precision, active, tile, flags, sigma, moduli), *bufs)
         if return_ru:
             extra = dict(R_aa=bufs[0], R_ab=bufs[1], U_aa=bufs[2], U_ab=bufs[3])
         return dict(d1=t[2], d2aa=t[3], d2ab=t[4], energy=E, norm2=n2, **extra)
@@ -363,7 +366,7 @@ class Context:
 
     def solve(self, h, V, d1, d2aa, d2ab, n_alpha, eps=1e-3, de_tol=1e-6, max_iter=100,
               control="fixed", max_halvings=8, eps_max=0.0, precision="fp64", active=None, tile=-1,
-              flags=0, capacity=256, sigma=None):
+              flags=0, capacity=256, sigma=None, moduli=0):
         """The Euler iteration of Eq. (9) with the stopping rules of the method
         section on device copies of the inputs (acse_solve).  Returns a dict with
         the final d1, d2aa, d2ab (device), energy/norm2 of the input and returned
@@ -373,7 +376,8 @@ class Context:
         so = SolveOptions(float(eps), float(de_tol), float(eps_max), int(max_iter),
                           CONTROLS[control] if isinstance(control, str) else int(control),
                           int(max_halvings), 0)
-        res, hist = self.solve_raw(prob, self.options(precision, active, tile, flags, sigma), so, capacity)
+        res, hist = self.solve_raw(prob, self.options(precision, active, tile, flags, sigma, moduli), so,
+                                   capacity)
         return dict(d1=t[2], d2aa=t[3], d2ab=t[4], energy0=res.energy0, norm2_0=res.norm2_0,
                     energy=res.energy, norm2=res.norm2, eps=res.eps, iterations=res.iterations,
                     trial_count=res.trials, maps=res.maps, stop=STOP_REASONS[res.stop],
@@ -575,14 +579,14 @@ class ACSEEnergy(torch.autograd.Function):
 # Options of ``Context.solve`` that change the iteration a checkpoint continues,
 # with their defaults there.
 _SOLVE_TAG_DEFAULTS = dict(de_tol=1e-6, control="fixed", max_halvings=8, eps_max=0.0, precision="fp64",
-                           active=None, sigma=None)
+                           active=None, sigma=None, moduli=0)
 
 
 def checkpoint_tag(h, V, n_alpha, **kw):
     """Hash naming the problem and the iteration of a ``solve_checkpointed`` file:
     h, V, n_alpha, the reconstruction (``sigma``), the precision of the
-    contractions, the active mask, the step control, max_halvings, eps_max and
-    de_tol (defaults as in ``Context.solve``).  The first step size is not part
+    contractions and its modulus count, the active mask, the step control,
+    max_halvings, eps_max and de_tol (defaults as in ``Context.solve``).  The first step size is not part
     of it: a resumed run continues with the step size the file holds."""
     import hashlib
     import numpy as np
@@ -601,7 +605,7 @@ def checkpoint_tag(h, V, n_alpha, **kw):
     precision = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
     active = None if opt["active"] is None else [bool(a) for a in opt["active"]]
     tag.update(repr((precision, active, control, int(opt["max_halvings"]), float(opt["eps_max"]).hex(),
-                     float(opt["de_tol"]).hex())).encode())
+                     float(opt["de_tol"]).hex(), int(opt["moduli"]))).encode())
     return tag.hexdigest()
 
 

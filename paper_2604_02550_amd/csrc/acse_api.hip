@@ -31,6 +31,7 @@
 #include <vector>
 
 #include "../../include/acse.h"
+#include "gemm_crt.h"
 #include "ny.h"
 #include "ny_plan.h"
 #include "tensor_ops.h"
@@ -110,6 +111,16 @@ struct acse_ctx_s {
   // set by acse_step around its update map: the 2-RDM has not changed since
   // the residual map, whose cumulant blocks and their operand layouts stand
   bool ny_reuse_d = false;
+  // exact-accumulation int8 products (ACSE_INT8CRT): residue planes and row
+  // exponents of the 12 operand buffers (allocated by the first such call, for
+  // r_max and the largest modulus count) and the table of the call's moduli
+  void *cbase = nullptr;
+  int64_t cbytes = 0;
+  int8_t *cres[12] = {};
+  int *cexp[12] = {};
+  int64_t cres_bytes = 0;  // bytes of one operand's residue buffer
+  CrtTable crt{};
+  int crt_moduli = 0;      // modulus count of the call in progress (set by validate)
 };
 
 namespace {
@@ -243,8 +254,14 @@ acse_status validate(acse_ctx c, const acse_problem *p, const acse_options *o, b
       (need_d1 && !aligned16(p->d1)))
     return fail(c, ACSE_ERR_ALIGN, "problem arrays must be 16-byte aligned");
   if (o) {
-    if (o->precision < ACSE_FP64 || o->precision > ACSE_BF16X3)
+    if (o->precision < ACSE_FP64 || o->precision > ACSE_INT8CRT)
       return fail(c, ACSE_ERR_ARG, "unknown precision");
+    if (o->moduli != 0 && (o->moduli < kMinModuli || o->moduli > kMaxModuli))
+      return fail(c, ACSE_ERR_ARG, "moduli must be 0 or in [" + std::to_string(kMinModuli) + ", " +
+                                       std::to_string(kMaxModuli) + "]");
+    if (o->precision == ACSE_INT8CRT && o->reconstruction == ACSE_RECON_NY)
+      return fail(c, ACSE_ERR_UNSUPPORTED, "the int8 exact-accumulation products are built for the Valdemoro "
+                                           "reconstruction only");
     if (o->tile < -1 || o->tile >= gemm_num_tiles(GEMM_F64))
       return fail(c, ACSE_ERR_ARG, "tile configuration out of range");
     if (o->flags & ~(ACSE_FLAG_GENERAL_KERNELS | ACSE_FLAG_CHECK_INPUTS))
@@ -259,6 +276,7 @@ acse_status validate(acse_ctx c, const acse_problem *p, const acse_options *o, b
     }
   }
   c->general = o && (o->flags & ACSE_FLAG_GENERAL_KERNELS);
+  c->crt_moduli = (o && o->precision == ACSE_INT8CRT) ? (o->moduli ? o->moduli : kDefaultModuli) : 0;
   c->ny_on = o && o->reconstruction == ACSE_RECON_NY;
   if (c->ny_on) {
     c->ny_sigma.assign(p->r, -1.0);
@@ -277,7 +295,93 @@ acse_status check_out(acse_ctx c, const void *p, const char *name) {
 
 GemmPrec prec_of(const acse_options *o) {
   if (!o) return GEMM_F64;
-  return o->precision == ACSE_FP32 ? GEMM_F32 : o->precision == ACSE_BF16X3 ? GEMM_BF16X3 : GEMM_F64;
+  switch (o->precision) {
+    case ACSE_FP32: return GEMM_F32;
+    case ACSE_BF16X3: return GEMM_BF16X3;
+    case ACSE_INT8CRT: return GEMM_I8CRT;
+    default: return GEMM_F64;
+  }
+}
+
+// Format the operand producers write: the int8 exact-accumulation products take
+// FP64 operands and convert them to residue planes afterwards.
+GemmPrec op_prec(GemmPrec prec) { return prec == GEMM_I8CRT ? GEMM_F64 : prec; }
+
+// Residue workspace of the int8 exact-accumulation products (first use), and
+// the moduli table of the call in progress.
+acse_status ensure_crt(acse_ctx c) {
+  if (!c->cbase) {
+    const int rm = c->r_max;
+    const int64_t rows = op_rows(rm);
+    c->cres_bytes = round_up((int64_t)kMaxModuli * rows * crt_ldr(rm * rm), 256);
+    const int64_t ebytes = round_up(rows * (int64_t)sizeof(int), 256);
+    const int64_t bytes = kNumOps * (c->cres_bytes + ebytes);
+    if (hipMalloc(&c->cbase, bytes) != hipSuccess) {
+      (void)hipGetLastError();
+      c->cbase = nullptr;
+      return fail(c, ACSE_ERR_NOMEM, "cannot allocate the int8 residue workspace (" + std::to_string(bytes) + " bytes)");
+    }
+    c->cbytes = bytes;
+    char *q = static_cast<char *>(c->cbase);
+    for (int k = 0; k < kNumOps; ++k) {
+      c->cres[k] = reinterpret_cast<int8_t *>(q);
+      q += c->cres_bytes;
+      c->cexp[k] = reinterpret_cast<int *>(q);
+      q += ebytes;
+    }
+  }
+  if (c->crt.nmod != c->crt_moduli && !crt_table(c->crt_moduli, c->crt))
+    return fail(c, ACSE_ERR_ARG, "no moduli table for " + std::to_string(c->crt_moduli) + " moduli");
+  return ACSE_OK;
+}
+
+// Rows, K and leading dimension of operand buffer idx at r (the layouts of
+// map_probs), and the K of the product it enters.
+struct OpShape { int rows, K, ld; };
+OpShape op_shape(int idx, int r) {
+  const int r2 = r * r, nlt = npair_lt(r), nle = npair_le(r);
+  const int ldlt = (int)ld_pair_lt(r), ldle = (int)ld_pair_le(r), ld = (int)op_ld(r);
+  switch (idx) {
+    case OP_DAA: return {nlt, nlt, ldlt};
+    case OP_DS: return {nle, nle, ldle};
+    case OP_DA: return {nlt, nlt, ldlt};
+    case OP_BAA: return {r2, nlt, ldlt};
+    case OP_BS: return {r2, nle, ldle};
+    case OP_BA: return {r2, nlt, ldlt};
+    default: return {r2, r2, ld};  // the ph operands L+-, L3, W'+-, W3
+  }
+}
+int64_t crt_plane(int idx, int r) { return op_rows(r) * crt_ldr(op_shape(idx, r).K); }
+
+// FP64 operands -> residue planes and row exponents.  rdm_side: the operands
+// built from the 2-RDM (the ph B and pp A sides), which carry the
+// reconstruction factors u_j; otherwise the X side (ph A and pp B).
+acse_status crt_residues(acse_ctx c, const Workspace &w, int r, bool rdm_side) {
+  static const int rdm_ops[6] = {OP_RP, OP_RM, OP_R3, OP_DAA, OP_DS, OP_DA};
+  static const int x_ops[6] = {OP_LP, OP_LM, OP_L3, OP_BAA, OP_BS, OP_BA};
+  const int *ops = rdm_side ? rdm_ops : x_ops;
+  ResidueBatch b{};
+  b.count = 6;
+  int rows = 0;
+  for (int q = 0; q < 6; ++q) {
+    const int idx = ops[q];
+    const OpShape sh = op_shape(idx, r);
+    ResidueJob &J = b.job[q];
+    J.src = reinterpret_cast<const double *>(w.op[idx]);
+    J.dst = c->cres[idx];
+    J.e = c->cexp[idx];
+    J.plane = crt_plane(idx, r);
+    J.row_begin = rows;
+    J.K = sh.K;
+    J.ld = sh.ld;
+    J.ldr = (int)crt_ldr(sh.K);
+    J.kbits = crt_kbits(c->crt, sh.K);
+    J.premul = rdm_side ? 1 : 0;
+    rows += sh.rows;
+  }
+  b.total_rows = rows;
+  HIP_TRY(c, launch_to_residues(b, c->crt, c->stream));
+  return ACSE_OK;
 }
 
 // Operands that depend only on (gamma, 2D): W natural, the ph B operands and
@@ -290,11 +394,13 @@ acse_status prep_rdm_operands(acse_ctx c, const acse_problem *p, GemmPrec prec, 
   const int r = p->r;
   const int ld = (int)op_ld(r);
   StageTimer timer(c, 0);
+  const GemmPrec op = op_prec(prec);
   HIP_TRY(c, launch_w_natural(r, p->d1, p->d2aa, p->d2ab, w.Waa, w.Wab, c->stream));
-  HIP_TRY(c, launch_w_ph(prec, r, ld, p->d1, p->d2aa, p->d2ab, operand(w, OP_RP, prec, r),
-                         operand(w, OP_RM, prec, r), operand(w, OP_R3, prec, r), c->stream));
-  HIP_TRY(c, launch_d_operand(prec, r, p->d2aa, p->d2ab, operand(w, OP_DAA, prec, r),
-                              operand(w, OP_DS, prec, r), operand(w, OP_DA, prec, r), c->stream));
+  HIP_TRY(c, launch_w_ph(op, r, ld, p->d1, p->d2aa, p->d2ab, operand(w, OP_RP, op, r),
+                         operand(w, OP_RM, op, r), operand(w, OP_R3, op, r), c->stream));
+  HIP_TRY(c, launch_d_operand(op, r, p->d2aa, p->d2ab, operand(w, OP_DAA, op, r),
+                              operand(w, OP_DS, op, r), operand(w, OP_DA, op, r), c->stream));
+  if (prec == GEMM_I8CRT) return crt_residues(c, w, r, true);
   return ACSE_OK;
 }
 
@@ -313,6 +419,12 @@ ModeArgs mode_base(acse_ctx c, int r, const double *g) {
 // Stage 2 of F(X): the O(r^4)/O(r^5) transforms that feed the products.
 acse_status map_front(acse_ctx c, const acse_problem *p, GemmPrec prec, const double *Xaa,
                       const double *Xab, Workspace &w) {
+  if (prec == GEMM_I8CRT) {
+    acse_status st = map_front(c, p, GEMM_F64, Xaa, Xab, w);
+    if (st != ACSE_OK) return st;
+    StageTimer t2(c, 2);
+    return crt_residues(c, w, p->r, false);
+  }
   const int r = p->r;
   const int64_t r2 = (int64_t)r * r, r3 = r2 * r;
   const int ld = (int)op_ld(r);
@@ -417,6 +529,27 @@ void map_probs(const Workspace &w, GemmPrec prec, int r, GemmProb *out) {
   set(3, OP_LP, OP_RP, 1.0, w.Pp, (int)r2, (int)r2, ld, r, r3, r2, 1);    // rows (k,i), cols (j,l) -> [i,j,k,l]
   set(4, OP_LM, OP_RM, 1.0, w.Pm, (int)r2, (int)r2, ld, r, r3, r2, 1);
   set(5, OP_L3, OP_R3, -2.0, w.E3, (int)r2, (int)r2, ld, r, r2, r3, 1);   // rows (k,j), cols (i,l) -> [i,j,k,l]
+}
+
+// The same six products on the residue planes of the int8 exact-accumulation mode.
+void map_probs_crt(acse_ctx c, int r, GemmProb *out) {
+  const Workspace &w = c->ws;
+  map_probs(w, GEMM_F64, r, out);  // outputs, shapes, alphas and store maps
+  static const int pa[6] = {OP_DAA, OP_DS, OP_DA, OP_LP, OP_LM, OP_L3};
+  static const int pb[6] = {OP_BAA, OP_BS, OP_BA, OP_RP, OP_RM, OP_R3};
+  for (int q = 0; q < kProbsPerMap; ++q) {
+    GemmProb &P = out[q];
+    const int K = op_shape(pa[q], r).K;
+    P.A = c->cres[pa[q]];
+    P.B = c->cres[pb[q]];
+    P.A2 = P.B2 = nullptr;
+    P.ld = P.Kp = (int)crt_ldr(K);
+    P.plane_a = crt_plane(pa[q], r);
+    P.plane_b = crt_plane(pb[q], r);
+    P.ea = c->cexp[pa[q]];
+    P.eb = c->cexp[pb[q]];
+    P.kshift = 2 * crt_kbits(c->crt, K);
+  }
 }
 
 int map_cfg(acse_ctx c, GemmPrec prec, int r, int cfg) {
@@ -682,6 +815,14 @@ acse_status run_map(acse_ctx c, const acse_problem *p, GemmPrec prec, int cfg, c
   if (st != ACSE_OK) return st;
   GemmBatch batch{};
   batch.count = kProbsPerMap;
+  if (prec == GEMM_I8CRT) {
+    map_probs_crt(c, r, batch.p);
+    {
+      StageTimer t3(c, 3);
+      HIP_TRY(c, gemm_crt_launch(batch, c->crt, c->stream));
+    }
+    return map_back(c, p, sigma, Oaa, Oab, act, Maa, Mab, w.scal + slot, w, Xaa, Xab, prec, cfg);
+  }
   map_probs(w, prec, r, batch.p);
   int use_cfg = cfg;
   if (use_cfg < 0) {
@@ -820,6 +961,7 @@ acse_status acse_destroy(acse_ctx ctx) {
   if (ctx->vbase) (void)hipFree(ctx->vbase);
   if (ctx->sbase) (void)hipFree(ctx->sbase);
   if (ctx->nybase) (void)hipFree(ctx->nybase);
+  if (ctx->cbase) (void)hipFree(ctx->cbase);
   if (ctx->bbase) (void)hipFree(ctx->bbase);
   if (ctx->hdesc) (void)hipHostFree(ctx->hdesc);
   if (ctx->hdesc_done) (void)hipEventDestroy(ctx->hdesc_done);
@@ -843,6 +985,7 @@ acse_status acse_residual(acse_ctx ctx, const acse_problem *prob, const acse_opt
                           double *R_aa, double *R_ab, double *norm2_host) {
   acse_status st = validate(ctx, prob, opts);
   if (st != ACSE_OK) return st;
+  if (ctx->crt_moduli && (st = ensure_crt(ctx)) != ACSE_OK) return st;
   if ((st = check_out(ctx, R_aa, "R_aa")) != ACSE_OK) return st;
   if ((st = check_out(ctx, R_ab, "R_ab")) != ACSE_OK) return st;
   HIP_TRY(ctx, hipSetDevice(ctx->device));
@@ -865,6 +1008,7 @@ acse_status acse_autotune(acse_ctx ctx, const acse_problem *prob, const acse_opt
                           int32_t *best_tile, double *times_ms) {
   acse_status st = validate(ctx, prob, opts);
   if (st != ACSE_OK) return st;
+  if (ctx->crt_moduli && (st = ensure_crt(ctx)) != ACSE_OK) return st;
   ctx->ny_on = false;  // the tile choice concerns the Valdemoro products; the NY ones share it
   if (!best_tile) return fail(ctx, ACSE_ERR_ARG, "best_tile is NULL");
   HIP_TRY(ctx, hipSetDevice(ctx->device));
@@ -923,6 +1067,7 @@ acse_status acse_update_map(acse_ctx ctx, const acse_problem *prob, const acse_o
                             const double *X_aa, const double *X_ab, double *U_aa, double *U_ab) {
   acse_status st = validate(ctx, prob, opts);
   if (st != ACSE_OK) return st;
+  if (ctx->crt_moduli && (st = ensure_crt(ctx)) != ACSE_OK) return st;
   if ((st = check_out(ctx, X_aa, "X_aa")) != ACSE_OK) return st;
   if ((st = check_out(ctx, X_ab, "X_ab")) != ACSE_OK) return st;
   if ((st = check_out(ctx, U_aa, "U_aa")) != ACSE_OK) return st;
@@ -954,6 +1099,7 @@ acse_status acse_step(acse_ctx ctx, acse_problem *prob, double eps, const acse_o
                       double *norm2_host) {
   acse_status st = validate(ctx, prob, opts);
   if (st != ACSE_OK) return st;
+  if (ctx->crt_moduli && (st = ensure_crt(ctx)) != ACSE_OK) return st;
   if (!std::isfinite(eps)) return fail(ctx, ACSE_ERR_ARG, "eps is not finite");
   for (const void *q : {static_cast<const void *>(R_aa), static_cast<const void *>(R_ab),
                         static_cast<const void *>(U_aa), static_cast<const void *>(U_ab)})
@@ -1043,6 +1189,8 @@ extern "C" acse_status acse_residual_noalloc(void *hip_stream, const acse_proble
                                             " outside [2, 16], the range of acse_residual_noalloc");
   if (opts && opts->reconstruction == ACSE_RECON_NY)
     return noalloc_fail(ACSE_ERR_UNSUPPORTED, "acse_residual_noalloc takes the Valdemoro reconstruction only");
+  if (opts && opts->precision == ACSE_INT8CRT)
+    return noalloc_fail(ACSE_ERR_UNSUPPORTED, "acse_residual_noalloc runs in FP64, FP32 or split BF16");
   if (norm2_dev && (reinterpret_cast<uintptr_t>(norm2_dev) & 7u))
     return noalloc_fail(ACSE_ERR_ALIGN, "norm2_dev must be 8-byte aligned");
   int dev = 0;
@@ -1134,6 +1282,8 @@ extern "C" acse_status acse_residual_vjp(acse_ctx ctx, const acse_problem *prob,
   acse_status st = validate(ctx, prob, opts);
   if (st != ACSE_OK) return st;
   if (ctx->ny_on) return fail(ctx, ACSE_ERR_UNSUPPORTED, "the adjoint is built for the Valdemoro reconstruction only");
+  if (ctx->crt_moduli)
+    return fail(ctx, ACSE_ERR_UNSUPPORTED, "the adjoint runs in FP64, FP32 or split BF16, not in int8 exact accumulation");
   for (const void *q : {static_cast<const void *>(Rbar_aa), static_cast<const void *>(Rbar_ab),
                         static_cast<const void *>(h_bar), static_cast<const void *>(V_bar),
                         static_cast<const void *>(d1_bar), static_cast<const void *>(d2aa_bar),
@@ -1677,6 +1827,9 @@ extern "C" acse_status acse_solve(acse_ctx ctx, acse_problem *prob, const acse_o
   const bool quad = so->control == ACSE_EULER_QUADRATIC;
   if (quad && ctx->ny_on)
     return fail(ctx, ACSE_ERR_UNSUPPORTED, "the quadratic control needs the adjoint, built for the Valdemoro reconstruction only");
+  if (quad && ctx->crt_moduli)
+    return fail(ctx, ACSE_ERR_UNSUPPORTED, "the quadratic control needs the adjoint, not built for int8 exact accumulation");
+  if (ctx->crt_moduli && (st = ensure_crt(ctx)) != ACSE_OK) return st;
   SolveWs sw{};
   if ((st = ensure_solve_ws(ctx, quad, sw)) != ACSE_OK) return st;
   if (quad && (st = ensure_vjp_ws(ctx)) != ACSE_OK) return st;
@@ -1871,6 +2024,9 @@ acse_status validate_batch(acse_ctx c, int32_t count, const acse_problem *probs,
   if (c->ny_on && opts->ny_sigma)
     return fail(c, ACSE_ERR_ARG, "a batch takes each instance's reference occupations from its n_alpha: "
                                  "ny_sigma must be NULL");
+  if (c->crt_moduli)
+    return fail(c, ACSE_ERR_UNSUPPORTED, "the batched residual runs in FP64, FP32 or split BF16, not in int8 "
+                                         "exact accumulation");
   return ACSE_OK;
 }
 

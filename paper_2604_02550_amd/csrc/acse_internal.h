@@ -18,7 +18,7 @@ namespace acse {
 // With ksplit > 1 each K chunk writes its own partial block at
 // C + split * split_stride (natural layout m * N + n).
 // ---------------------------------------------------------------------------
-enum GemmPrec { GEMM_F64 = 0, GEMM_F32 = 1, GEMM_BF16X3 = 2 };
+enum GemmPrec { GEMM_F64 = 0, GEMM_F32 = 1, GEMM_BF16X3 = 2, GEMM_I8CRT = 3 };
 
 struct GemmProb {
   const void *A;      // plane 0 (hi for bf16x3)
@@ -33,6 +33,13 @@ struct GemmProb {
   int ksplit, kchunk; // K chunks (kchunk multiple of the K tile)
   int tiles_m, tiles_n, tile_begin;
   int accumulate;     // 1: C += alpha * AB^T
+  // exact-accumulation int8 products only (gemm_crt.hip): residue planes of A
+  // and B lie plane_a / plane_b bytes apart, ea / eb are the row exponents
+  // and kshift the total scaling bits 2k
+  const int *ea;
+  const int *eb;
+  int64_t plane_a, plane_b;
+  int kshift;
 };
 
 constexpr int kMaxGemmProbs = 10;  // the by-value batch stays within the 4 KiB kernel-argument limit (2.3 KiB)

@@ -31,7 +31,8 @@ GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "r50
 # relative to the largest stored sample of the array
 TOL = {"fp64": (1e-10, 1e-10, 1e-14, 1e-10),
        "fp32": (1e-5, 5e-6, 1e-6, 1e-7),
-       "bf16x3": (5e-5, 2e-5, 2e-6, 1e-6)}
+       "bf16x3": (5e-5, 2e-5, 2e-6, 1e-6),
+       "int8crt": (1e-10, 1e-10, 1e-13, 1e-10)}
 
 
 @pytest.fixture(scope="module")
@@ -53,7 +54,7 @@ def r50(acse):
     ctx.close()
 
 
-@pytest.mark.parametrize("precision", ["fp64", "fp32", "bf16x3"])
+@pytest.mark.parametrize("precision", ["fp64", "fp32", "bf16x3", "int8crt"])
 def test_r50_step_vs_stored_oracle(r50, precision):
     acse, ctx, g, p = r50
     print(f"[fullsize] r50 step precision={precision}", flush=True)
@@ -77,7 +78,8 @@ def test_r50_step_vs_stored_oracle(r50, precision):
         assert np.abs(got[idx] - ref).max() <= max(tU * g["eps"] * umax, 1e-12 * np.abs(ref).max()), key
     dE = abs(out["energy"] - g["energy1"])
     assert dE <= tE * abs(g["energy1"] - g["energy0"])
-    if precision == "fp64":
+    print(f"[fullsize] r50 {precision}: |dE| = {dE:.3e} Eh", flush=True)
+    if precision in ("fp64", "int8crt"):
         assert dE < 1e-7
     assert abs(out["norm2"] - g["norm2"]) <= tN * g["norm2"]
     # the 1-RDM sums r elements of the new 2-RDM per entry, times 2 / (N - 1)
@@ -86,10 +88,11 @@ def test_r50_step_vs_stored_oracle(r50, precision):
     assert np.abs(out["d1"].cpu().numpy() - g1).max() <= max(fac * tU * g["eps"] * umax, 1e-12 * np.abs(g1).max())
 
 
-def test_r96_determinant_closed_form(acse):
+@pytest.mark.parametrize("precision", ["fp64", "int8crt"])
+def test_r96_determinant_closed_form(acse, precision):
     r, na = 96, 29
     eps = 1e-6  # eps ||R||^2 is a few percent of |E|: the energy identity is well conditioned
-    print(f"[fullsize] r={r} closed-shell determinant, n_alpha={na}", flush=True)
+    print(f"[fullsize] r={r} closed-shell determinant, n_alpha={na}, {precision}", flush=True)
     rng = np.random.default_rng(96)
     h, V = gen.hamiltonian(rng, r, 96)
     g, d2aa, d2ab = dform.rdms(r, na)
@@ -104,7 +107,7 @@ def test_r96_determinant_closed_form(acse):
     del caa, cab
     ctx = acse.Context(r_max=r)
     try:
-        Raa, Rab, gn2 = ctx.residual(*inputs, na)
+        Raa, Rab, gn2 = ctx.residual(*inputs, na, precision=precision)
         scale = max(np.abs(exp_aa).max(), np.abs(exp_ab).max())
         assert np.abs(Raa.cpu().numpy() - exp_aa).max() <= 1e-10 * scale
         assert np.abs(Rab.cpu().numpy() - exp_ab).max() <= 1e-10 * scale
@@ -112,7 +115,7 @@ def test_r96_determinant_closed_form(acse):
         assert abs(gn2 - n2) <= 1e-10 * n2
         ge = ctx.energy(inputs[0], inputs[1], inputs[3], inputs[4], na)
         assert abs(ge - e0) <= 1e-10 * abs(e0)
-        out = ctx.step(*inputs, na, eps=eps, return_ru=True)
+        out = ctx.step(*inputs, na, eps=eps, return_ru=True, precision=precision)
         assert abs(out["norm2"] - n2) <= 1e-10 * n2
         assert abs((out["energy"] - ge) + eps * n2) <= 1e-9 * eps * n2
         Uaa, Uab = out["U_aa"], out["U_ab"]
