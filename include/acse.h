@@ -96,9 +96,10 @@ typedef enum {
                       adjoint, the quadratic control, the batched residual, the NY
                       reconstruction and acse_residual_noalloc are
                       ACSE_ERR_UNSUPPORTED with it.  The first call allocates residue
-                      buffers for r_max: 12 x (15 x op_rows x round_up(r_max^2, 128) +
-                      4 op_rows) bytes, op_rows = r_max^2 rounded up to 256 (1.2 GB at
-                      r_max = 50). */
+                      buffers for r_max: 12 x (15 x op_rows x round_up(r_max^2, 256) +
+                      4 op_rows) bytes for the operands (op_rows = r_max^2 rounded up to
+                      256) and 15 x about 4.5 r_max^4 bytes for the products' residues
+                      (1.6 GB in all at r_max = 50). */
 } acse_precision;
 
 typedef struct {

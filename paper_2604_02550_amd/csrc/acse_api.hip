@@ -119,6 +119,7 @@ struct acse_ctx_s {
   int8_t *cres[12] = {};
   int *cexp[12] = {};
   int64_t cres_bytes = 0;  // bytes of one operand's residue buffer
+  int8_t *cy = nullptr;    // residues of the six products (all moduli)
   CrtTable crt{};
   int crt_moduli = 0;      // modulus count of the call in progress (set by validate)
 };
@@ -307,6 +308,13 @@ GemmPrec prec_of(const acse_options *o) {
 // FP64 operands and convert them to residue planes afterwards.
 GemmPrec op_prec(GemmPrec prec) { return prec == GEMM_I8CRT ? GEMM_F64 : prec; }
 
+// Bytes of the six products' residues for one modulus at r (rows in fours).
+int64_t crt_out_bytes_per_modulus(int r) {
+  const int r2 = r * r;
+  return 3 * crt_residue_out_bytes(r2, r2) + 2 * crt_residue_out_bytes(npair_lt(r), r2) +
+         crt_residue_out_bytes(npair_le(r), r2);
+}
+
 // Residue workspace of the int8 exact-accumulation products (first use), and
 // the moduli table of the call in progress.
 acse_status ensure_crt(acse_ctx c) {
@@ -315,7 +323,8 @@ acse_status ensure_crt(acse_ctx c) {
     const int64_t rows = op_rows(rm);
     c->cres_bytes = round_up((int64_t)kMaxModuli * rows * crt_ldr(rm * rm), 256);
     const int64_t ebytes = round_up(rows * (int64_t)sizeof(int), 256);
-    const int64_t bytes = kNumOps * (c->cres_bytes + ebytes);
+    const int64_t ybytes = round_up(kMaxModuli * crt_out_bytes_per_modulus(rm), 256);
+    const int64_t bytes = kNumOps * (c->cres_bytes + ebytes) + ybytes;
     if (hipMalloc(&c->cbase, bytes) != hipSuccess) {
       (void)hipGetLastError();
       c->cbase = nullptr;
@@ -329,6 +338,7 @@ acse_status ensure_crt(acse_ctx c) {
       c->cexp[k] = reinterpret_cast<int *>(q);
       q += ebytes;
     }
+    c->cy = reinterpret_cast<int8_t *>(q);
   }
   if (c->crt.nmod != c->crt_moduli && !crt_table(c->crt_moduli, c->crt))
     return fail(c, ACSE_ERR_ARG, "no moduli table for " + std::to_string(c->crt_moduli) + " moduli");
@@ -537,6 +547,7 @@ void map_probs_crt(acse_ctx c, int r, GemmProb *out) {
   map_probs(w, GEMM_F64, r, out);  // outputs, shapes, alphas and store maps
   static const int pa[6] = {OP_DAA, OP_DS, OP_DA, OP_LP, OP_LM, OP_L3};
   static const int pb[6] = {OP_BAA, OP_BS, OP_BA, OP_RP, OP_RM, OP_R3};
+  int64_t yoff = 0;
   for (int q = 0; q < kProbsPerMap; ++q) {
     GemmProb &P = out[q];
     const int K = op_shape(pa[q], r).K;
@@ -549,6 +560,9 @@ void map_probs_crt(acse_ctx c, int r, GemmProb *out) {
     P.ea = c->cexp[pa[q]];
     P.eb = c->cexp[pb[q]];
     P.kshift = 2 * crt_kbits(c->crt, K);
+    P.Y = c->cy + yoff;
+    P.plane_y = crt_residue_out_bytes(P.M, P.N);
+    yoff += (int64_t)c->crt.nmod * P.plane_y;
   }
 }
 

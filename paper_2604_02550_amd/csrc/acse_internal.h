@@ -40,6 +40,8 @@ struct GemmProb {
   const int *eb;
   int64_t plane_a, plane_b;
   int kshift;
+  int8_t *Y;          // residues of the product per modulus: plane j at Y + j * plane_y,
+  int64_t plane_y;    // rows grouped by four: byte (m / 4, n, m % 4)
 };
 
 constexpr int kMaxGemmProbs = 10;  // the by-value batch stays within the 4 KiB kernel-argument limit (2.3 KiB)

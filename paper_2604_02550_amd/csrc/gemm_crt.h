@@ -44,9 +44,17 @@ struct ResidueBatch {
 };
 hipError_t launch_to_residues(const ResidueBatch &b, const CrtTable &T, hipStream_t s);
 
-// Grouped modular product: for each problem, A and B point at plane 0 of the
-// residue operands (planes plane_a / plane_b bytes apart, rows of ld bytes,
-// Kp = ld a multiple of kCrtKPad), ea / eb the row exponents and kshift = 2k.
+// Per-XCD ranges of the per-modulus tile order of the modular product.
+struct ModSched {
+  int xs[kGemmXcds + 1];
+};
+
+// Grouped modular product and reconstruction: for each problem, A and B point
+// at plane 0 of the residue operands (planes plane_a / plane_b bytes apart,
+// rows of ld bytes, Kp = ld a multiple of kCrtKPad), ea / eb the row
+// exponents, kshift = 2k, and Y at crt_residue_out_bytes(M, N) bytes per
+// modulus for the residues of the product.  Writes C through the store map.
 hipError_t gemm_crt_launch(GemmBatch &b, const CrtTable &T, hipStream_t s);
+int64_t crt_residue_out_bytes(int M, int N);
 
 }  // namespace acse

@@ -10,21 +10,21 @@
 //      each residue in the int8 range; one operand carries the factor
 //      u_j = (M/m_j)^-1 mod m_j (M = prod m_j);
 //   3. one int8 MFMA product per modulus, accumulated exactly in int32
-//      (|sum| <= K 128^2 < 2^31 for K < 131072);
-//   4. y_j = acc_j mod m_j, and sum_j (M/m_j) y_j = A_int B_int^T (mod M);
-//      with K 2^(2k) < M/4 the representative of smallest magnitude is the
-//      exact integer product;
+//      (|sum| <= K 128^2 < 2^31 for K < 131072), reduced to a residue
+//      y_j = acc_j mod m_j in the int8 range and stored;
+//   4. sum_j (M/m_j) y_j = A_int B_int^T (mod M); with K 2^(2k) < M/4 the
+//      representative of smallest magnitude is the exact integer product;
 //   5. C = alpha * that integer * 2^(ea[m] + eb[n] - 2k), written through the
 //      same 4-index store map as the floating-point products.
 // The reconstruction runs in FP64: sum_j s1_j y_j is exact (s1_j = M/m_j with
-// its low bits cleared, at most 41 significant bits), sum_j s2_j y_j carries
-// the rest, and the multiple of M is removed from the exact part first.
+// its low bits cleared, at most 41 significant bits, |y_j| <= 128), sum_j
+// s2_j y_j carries the rest, and the multiple of M is removed from the exact
+// part first.
 //
-// Kernel: 8 wavefronts (2 x 4) own a 128 x 128 tile, each wave 64 x 32 made
-// of 16 x 16 blocks of v_mfma_i32_16x16x64_i8.  The loop runs over
-// (modulus, K slab) pairs with double-buffered LDS slabs; after the last slab
-// of a modulus the int32 accumulators are reduced and added to the two FP64
-// reconstruction sums, then cleared.
+// Kernels: the residue conversion of the operands (one block per row), the
+// modular product (256 x 256 tiles, one modulus per tile; 8 wavefronts of
+// 128 x 64 on v_mfma_i32_32x32x32_i8; K slabs loaded straight into LDS) and
+// the reconstruction (one thread per four rows of one column).
 #include <algorithm>
 #include <cmath>
 
@@ -32,44 +32,43 @@
 
 namespace acse {
 
-static_assert(sizeof(GemmBatch) + sizeof(CrtTable) <= 4096 - 64, "kernel arguments must fit in 4 KiB");
+static_assert(sizeof(GemmBatch) + sizeof(CrtTable) + sizeof(ModSched) <= 4096 - 64, "kernel arguments must fit in 4 KiB");
 static_assert(sizeof(ResidueBatch) + sizeof(CrtTable) <= 4096 - 64, "kernel arguments must fit in 4 KiB");
 
 namespace {
 
 typedef int32_t v4i __attribute__((ext_vector_type(4)));
 
-constexpr int kBM = 128, kBN = 128, kBK = 256;  // tile rows, columns, K bytes per slab
+constexpr int kBM = 256, kBN = 256, kBK = 128;  // tile rows, columns, K bytes per slab
 constexpr int kNT = 512;                        // 8 wavefronts
-constexpr int kLDK = kBK + 16;                  // LDS row stride (bytes): 16 rows of a
-                                                // 16-byte fragment read fall in distinct banks
 constexpr int kGroupM = 8;
 
-// XCD-aware logical workgroup index (the dispatcher deals workgroups round-robin
-// over the 8 XCDs, each with its own L2): every XCD receives a contiguous range.
-__device__ inline int xcd_logical_crt(int hw, int n) {
-  const int xcd = hw % kGemmXcds, kx = hw / kGemmXcds;
-  const int q8 = n / kGemmXcds, rem8 = n % kGemmXcds;
-  return xcd < rem8 ? xcd * (q8 + 1) + kx : rem8 * (q8 + 1) + (xcd - rem8) * q8 + kx;
-}
-
+typedef int32_t v16i __attribute__((ext_vector_type(16)));
 typedef __attribute__((address_space(3))) void lds_void_t;
 typedef __attribute__((address_space(1))) const void gbl_void_t;
 
-__device__ __forceinline__ void crt_tile(const GemmProb &P, const CrtTable &T, int local) {
-  constexpr int WTM = kBM / 2, WTN = kBN / 4;  // 64 x 32 per wave
-  constexpr int FM = WTM / 16, FN = WTN / 16;  // 4 x 2 MFMA blocks
-  constexpr int NKK = kBK / 64;                // MFMA steps per slab
-  constexpr int ROWB = kBK;                    // LDS row: 16 slots of 16 bytes, no padding
+// One 256 x 256 tile of one product for one modulus: C_j = A_j B_j^T, reduced
+// to residues y = C_j mod m_j in [-128, 128] (stored as bytes; y = 128 only
+// for m = 256, where the byte -128 is the same residue).
+__device__ __forceinline__ void mod_tile(const GemmProb &P, const CrtTable &T, int j, int local) {
+  constexpr int WTM = kBM / 2, WTN = kBN / 4;  // 128 x 64 per wave
+  constexpr int FM = WTM / 32, FN = WTN / 32;  // 4 x 2 blocks of 32 x 32
+  constexpr int NKK = kBK / 32;                // MFMA steps per slab
+  constexpr int ROWB = kBK;                    // LDS row: 8 slots of 16 bytes, no padding
   constexpr int LPW = kBM * kBK / 1024 / (kNT / 64);  // 1 KB direct loads per wave per operand
-  static_assert(kBK == 256, "the LDS swizzle assumes 16 slots of 16 bytes per row");
-  static_assert(LPW * 1024 * (kNT / 64) == kBM * kBK, "tile must split into whole wave loads");
+  static_assert(kBK == 128 && LPW == 4, "the LDS swizzle and load mapping assume 128-byte rows");
   static_assert(NKK >= 4 && NKK % 2 == 0, "pipelined loop needs an even step count >= 4");
-  // LDS slot of logical 16-byte chunk c of row r: c ^ (r % 16).  The 16 rows a
-  // fragment read takes (one chunk each) then fall on 16 distinct slots, i.e.
-  // all 64 banks, and a direct load still fills 1 KB (4 rows) contiguously.
-  __shared__ __attribute__((aligned(1024))) int8_t As[2][kBM * ROWB];
-  __shared__ __attribute__((aligned(1024))) int8_t Bs[2][kBN * ROWB];
+  // LDS slot of logical 16-byte chunk c of row r: c ^ ((r / 2) % 8).  The 16
+  // rows a quarter-wave of a fragment read takes (same chunk) then cover all
+  // 64 banks once (two rows share a 256-byte bank line), and a direct load
+  // still fills 1 KB (8 rows) contiguously.
+  // Two stages of A and B, each its own array: the loads of one stage and the
+  // fragment reads of the other then provably touch different LDS objects,
+  // so no wait for the loads in flight is inserted before those reads.
+  __shared__ __attribute__((aligned(1024))) int8_t As0[kBM * ROWB];
+  __shared__ __attribute__((aligned(1024))) int8_t As1[kBM * ROWB];
+  __shared__ __attribute__((aligned(1024))) int8_t Bs0[kBN * ROWB];
+  __shared__ __attribute__((aligned(1024))) int8_t Bs1[kBN * ROWB];
 
   // grouped tile order: kGroupM tile rows sweep the columns together
   const int in_group = kGroupM * P.tiles_n;
@@ -79,66 +78,60 @@ __device__ __forceinline__ void crt_tile(const GemmProb &P, const CrtTable &T, i
   const int lg = local - group * in_group;
   const int m0 = (first_m + lg % gsz) * kBM, n0 = (lg / gsz) * kBN;
   const int nk = P.Kp / kBK;
-  const int nmod = T.nmod;
-  const int total = nk * nmod;
 
   const int tid = threadIdx.x;
   const int lane = tid & 63;
   const int wave = tid >> 6;
   const int wm0 = (wave >> 2) * WTM, wn0 = (wave & 3) * WTN;
-  const int8_t *Ab = static_cast<const int8_t *>(P.A);
-  const int8_t *Bb = static_cast<const int8_t *>(P.B);
+  const int8_t *Ab = static_cast<const int8_t *>(P.A) + j * P.plane_a;
+  const int8_t *Bb = static_cast<const int8_t *>(P.B) + j * P.plane_b;
 
   // Direct loads: load q of this wave fills LDS bytes [(wave LPW + q) KB, +1 KB)
-  // = rows 16 wave + 4 q + lane / 16 (LPW = 4); lane l fetches the chunk that
-  // belongs in slot l % 16 of its row, chunk (l % 16) ^ (row % 16) = c0 ^ 4q.
-  static_assert(LPW == 4, "row r % 16 = 4 q + lane / 16 needs four loads per wave");
-  const int c0 = (lane & 15) ^ (lane >> 4);
-  const uint32_t ra0 = (uint32_t)((m0 + 16 * wave + (lane >> 4)) * P.ld);
-  const uint32_t rb0 = (uint32_t)((n0 + 16 * wave + (lane >> 4)) * P.ld);
-  const uint32_t ld4 = (uint32_t)(4 * P.ld);
-  auto glds = [&](int it, int buf) {
-    const int j = it / nk, kt = it - j * nk;
-    const int8_t *a = Ab + j * P.plane_a + kt * kBK;
-    const int8_t *b = Bb + j * P.plane_b + kt * kBK;
+  // = rows 32 wave + 8 q + lane / 8; lane l fetches the chunk that belongs in
+  // slot l % 8 of its row: chunk (l % 8) ^ ((row / 2) % 8) = (l % 8) ^ ((4 q + l / 16) % 8).
+  const uint32_t ra0 = (uint32_t)((m0 + 32 * wave + (lane >> 3)) * P.ld);
+  const uint32_t rb0 = (uint32_t)((n0 + 32 * wave + (lane >> 3)) * P.ld);
+  const uint32_t ld8 = (uint32_t)(8 * P.ld);
+  auto glds = [&](int kt, int8_t *as, int8_t *bs) {
+    const int8_t *a = Ab + kt * kBK;
+    const int8_t *b = Bb + kt * kBK;
 #pragma unroll
     for (int q = 0; q < LPW; ++q) {
       const int lds_off = (wave * LPW + q) * 1024;
-      const uint32_t col = (uint32_t)((c0 ^ (4 * q)) * 16) + q * ld4;
-      __builtin_amdgcn_global_load_lds((gbl_void_t *)(a + ra0 + col), (lds_void_t *)(&As[buf][lds_off]), 16, 0, 0);
-      __builtin_amdgcn_global_load_lds((gbl_void_t *)(b + rb0 + col), (lds_void_t *)(&Bs[buf][lds_off]), 16, 0, 0);
+      const uint32_t col = (uint32_t)(((lane & 7) ^ ((4 * q + (lane >> 4)) & 7)) * 16) + q * ld8;
+      __builtin_amdgcn_global_load_lds((gbl_void_t *)(a + ra0 + col), (lds_void_t *)(as + lds_off), 16, 0, 0);
+      __builtin_amdgcn_global_load_lds((gbl_void_t *)(b + rb0 + col), (lds_void_t *)(bs + lds_off), 16, 0, 0);
     }
   };
 
-  v4i acc[FM][FN];
-  double c1[FM][FN][4], c2[FM][FN][4];
+  v16i acc[FM][FN];
 #pragma unroll
   for (int i = 0; i < FM; ++i)
 #pragma unroll
-    for (int j = 0; j < FN; ++j) {
-      acc[i][j] = v4i{0, 0, 0, 0};
+    for (int jj = 0; jj < FN; ++jj)
 #pragma unroll
-      for (int v = 0; v < 4; ++v) { c1[i][j][v] = 0.0; c2[i][j][v] = 0.0; }
-    }
+      for (int v = 0; v < 16; ++v) acc[i][jj][v] = 0;
 
-  const int lrow = lane & 15;
-  const int lgrp = lane >> 4;
+  // fragment reads: lane l takes row (block base + l % 32), chunk 2 step + l / 32
+  const int lrow = lane & 31;
+  const int lhalf = lane >> 5;
+  const int swz = (lrow >> 1) & 7;  // block bases are multiples of 32
   v4i fa[2][FM], fb[2][FN];
-  auto fread = [&](int q, int b, int step) {
-    const int slot = ((step * 4 + lgrp) ^ lrow) * 16;  // rows of a fragment are 16-aligned
+  auto fread = [&](int q, const int8_t *as, const int8_t *bs, int step) {
+    const int slot = ((2 * step + lhalf) ^ swz) * 16;
 #pragma unroll
     for (int i = 0; i < FM; ++i)
-      fa[q][i] = *reinterpret_cast<const v4i *>(&As[b][(wm0 + i * 16 + lrow) * ROWB + slot]);
+      fa[q][i] = *reinterpret_cast<const v4i *>(as + (wm0 + i * 32 + lrow) * ROWB + slot);
 #pragma unroll
-    for (int j = 0; j < FN; ++j)
-      fb[q][j] = *reinterpret_cast<const v4i *>(&Bs[b][(wn0 + j * 16 + lrow) * ROWB + slot]);
+    for (int jj = 0; jj < FN; ++jj)
+      fb[q][jj] = *reinterpret_cast<const v4i *>(bs + (wn0 + jj * 32 + lrow) * ROWB + slot);
   };
   auto mma = [&](int q) {
 #pragma unroll
     for (int i = 0; i < FM; ++i)
 #pragma unroll
-      for (int j = 0; j < FN; ++j)
-        acc[i][j] = __builtin_amdgcn_mfma_i32_16x16x64_i8(fa[q][i], fb[q][j], acc[i][j], 0, 0, 0);
+      for (int jj = 0; jj < FN; ++jj)
+        acc[i][jj] = __builtin_amdgcn_mfma_i32_32x32x32_i8(fa[q][i], fb[q][jj], acc[i][jj], 0, 0, 0);
   };
 
   // Software-pipelined slab loop: the fragments of two MFMA steps are in
@@ -146,93 +139,123 @@ __device__ __forceinline__ void crt_tile(const GemmProb &P, const CrtTable &T, i
   // the next slab.  One barrier per slab, before the last step: after it every
   // wave's direct loads of the next slab have landed and every read of this
   // slab has completed, so the loads of the slab after next go into this
-  // slab's buffer right away (they have about one slab of MFMAs to arrive).
-  // Past the last slab the loads repeat the last one into the free buffer.
-  glds(0, 0);
-  glds(min(1, total - 1), 1);
+  // slab's buffer right away.  Past the last slab the loads repeat the last one.
+  // One slab from stage (ac, bc); the next one is in (an, bn).
+  auto slab = [&](int kt, int8_t *ac, int8_t *bc, int8_t *an, int8_t *bn) {
+#pragma unroll
+    for (int s = 0; s < NKK; ++s) {
+      mma(s & 1);
+      __builtin_amdgcn_sched_barrier(0);
+      if (s + 2 < NKK) {
+        fread(s & 1, ac, bc, s + 2);
+      } else {
+        if (s == NKK - 2) {
+          __builtin_amdgcn_s_waitcnt(0);  // this wave's loads of the next slab
+          __syncthreads();
+          glds(min(kt + 2, nk - 1), ac, bc);
+        }
+        fread(s & 1, an, bn, s + 2 - NKK);
+      }
+      __builtin_amdgcn_sched_barrier(0);
+    }
+  };
+  glds(0, As0, Bs0);
+  glds(min(1, nk - 1), As1, Bs1);
   __builtin_amdgcn_s_waitcnt(0);
   __syncthreads();
-  fread(0, 0, 0);
+  fread(0, As0, Bs0, 0);
   __builtin_amdgcn_sched_barrier(0);
-  fread(1, 0, 1);
+  fread(1, As0, Bs0, 1);
   __builtin_amdgcn_sched_barrier(0);
-  int it = 0;
-  for (int j = 0; j < nmod; ++j) {
-    for (int kt = 0; kt < nk; ++kt, ++it) {
-      const int cur = it & 1;
-#pragma unroll
-      for (int s = 0; s < NKK; ++s) {
-        mma(s & 1);
-        __builtin_amdgcn_sched_barrier(0);
-        if (s + 2 < NKK) {
-          fread(s & 1, cur, s + 2);
-        } else {
-          if (s == NKK - 2) {
-            __builtin_amdgcn_s_waitcnt(0);  // this wave's loads of the next slab
-            __syncthreads();
-            glds(min(it + 2, total - 1), cur);
-          }
-          fread(s & 1, cur ^ 1, s + 2 - NKK);
-        }
-        __builtin_amdgcn_sched_barrier(0);
-      }
-    }
-    // modulus j complete.  Any y = acc (mod m) with |y| <= 128 keeps the
-    // exact part of the reconstruction exact (41 + 7 bits per term, at most 15
-    // terms), so y = acc - m rint(acc / m) needs no range correction.
-    const double m = T.m[j], inv_m = T.inv_m[j], s1 = T.s1[j], s2 = T.s2[j];
-#pragma unroll
-    for (int i = 0; i < FM; ++i)
-#pragma unroll
-      for (int jj = 0; jj < FN; ++jj) {
-#pragma unroll
-        for (int v = 0; v < 4; ++v) {
-          const double a = (double)acc[i][jj][v];
-          const double y = fma(-rint(a * inv_m), m, a);
-          c1[i][jj][v] = fma(s1, y, c1[i][jj][v]);
-          c2[i][jj][v] = fma(s2, y, c2[i][jj][v]);
-        }
-        acc[i][jj] = v4i{0, 0, 0, 0};
-      }
+  int kt = 0;
+  for (; kt + 1 < nk; kt += 2) {
+    slab(kt, As0, Bs0, As1, Bs1);
+    slab(kt + 1, As1, Bs1, As0, Bs0);
   }
+  if (kt < nk) slab(kt, As0, Bs0, As1, Bs1);
 
-  // --- epilogue: integer product, scaling, (m, n) -> permuted 4-index address
-  const double alpha = P.alpha;
-  double *C = P.C;
-  const int rdiv = P.rdiv;
-  const double M1 = T.M1, M2 = T.M2, inv_M = T.inv_M;
+  // residues, four consecutive rows of one column per 32-bit store:
+  // accumulator item v of lane l is row 8 (v / 4) + 4 (l / 32) + v % 4, column l % 32
+  const double m = T.m[j], inv_m = T.inv_m[j];
+  int8_t *Y = P.Y + j * P.plane_y;
 #pragma unroll
-  for (int i = 0; i < FM; ++i) {
+  for (int i = 0; i < FM; ++i)
 #pragma unroll
-    for (int j = 0; j < FN; ++j) {
-      const int n = n0 + wn0 + j * 16 + lrow;
-      if (n >= P.N) continue;
-      const int64_t noff = (int64_t)(n / rdiv) * P.sn1 + (int64_t)(n % rdiv) * P.sn0;
-      const int en = P.eb[n] - P.kshift;
+    for (int jj = 0; jj < FN; ++jj) {
+      const int n = n0 + wn0 + jj * 32 + lrow;
 #pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        // accumulator item v of lane l is row 4 (l / 16) + v, column l % 16
-        const int m = m0 + wm0 + i * 16 + (lane >> 4) * 4 + v;
-        if (m >= P.M) continue;
-        const double q = rint((c1[i][j][v] + c2[i][j][v]) * inv_M);
-        const double cint = fma(-q, M1, c1[i][j][v]) + fma(-q, M2, c2[i][j][v]);
-        const double val = alpha * ldexp(cint, P.ea[m] + en);
-        const int64_t off = (int64_t)(m / rdiv) * P.sm1 + (int64_t)(m % rdiv) * P.sm0 + noff;
-        if (P.accumulate) C[off] += val; else C[off] = val;
+      for (int g = 0; g < 4; ++g) {
+        const int row = m0 + wm0 + i * 32 + 8 * g + 4 * lhalf;
+        uint32_t w = 0;
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+          const double a = (double)acc[i][jj][4 * g + t];
+          const int y = (int)fma(-rint(a * inv_m), m, a);
+          w |= (uint32_t)(y & 255) << (8 * t);
+        }
+        if (row < P.M && n < P.N) *reinterpret_cast<uint32_t *>(Y + ((int64_t)(row >> 2) * P.N + n) * 4) = w;
       }
     }
-  }
 }
 
+// Work of the modular product: every (modulus, product, tile).  Each XCD
+// (own L2) works through its share of every product (the c-th eighth of each,
+// as seg_* lists them) modulus by modulus, so all XCDs are on the same modulus
+// at about the same time and its operand planes (about 1/13 of the total)
+// stay cached.  sched.xs[c] .. xs[c+1]: XCD c's range of the per-modulus
+// logical tile list.
 __global__ void __launch_bounds__(kNT) __attribute__((amdgpu_waves_per_eu(2)))
-gemm_crt_kernel(const GemmBatch batch, const CrtTable tab) {
-  const int bid = xcd_logical_crt(blockIdx.x, batch.total_tiles);
+gemm_mod_kernel(const GemmBatch batch, const CrtTable tab, const ModSched sched) {
+  const int c = blockIdx.x % kGemmXcds, s = blockIdx.x / kGemmXcds;
+  const int share = sched.xs[c + 1] - sched.xs[c];
+  if (share == 0) return;
+  const int j = s / share;
+  if (j >= tab.nmod) return;
+  const int t = sched.xs[c] + (s - j * share);
   int lo = 0, hi = batch.nseg - 1;
   while (lo < hi) {
     const int mid = (lo + hi + 1) >> 1;
-    if (batch.seg_start[mid] <= bid) lo = mid; else hi = mid - 1;
+    if (batch.seg_start[mid] <= t) lo = mid; else hi = mid - 1;
   }
-  crt_tile(batch.p[batch.seg_prob[lo]], tab, batch.seg_local[lo] + bid - batch.seg_start[lo]);
+  mod_tile(batch.p[batch.seg_prob[lo]], tab, j, batch.seg_local[lo] + t - batch.seg_start[lo]);
+}
+
+// Reconstruction: one thread per (product, row quad, column).
+__global__ void __launch_bounds__(256) k_crt_combine(const GemmBatch batch, const CrtTable T) {
+  const GemmProb &P = batch.p[blockIdx.y];
+  const int64_t idx = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  const int64_t nquad = (P.M + 3) / 4;
+  if (idx >= nquad * P.N) return;
+  const int q = (int)(idx / P.N), n = (int)(idx - (int64_t)q * P.N);
+  double c1[4] = {0.0, 0.0, 0.0, 0.0}, c2[4] = {0.0, 0.0, 0.0, 0.0};
+  const int8_t *Y = P.Y + idx * 4;
+  // every modulus' word in flight at once, then the sums
+  uint32_t w[kMaxModuli];
+#pragma unroll
+  for (int j = 0; j < kMaxModuli; ++j)
+    w[j] = j < T.nmod ? *reinterpret_cast<const uint32_t *>(Y + j * P.plane_y) : 0u;
+#pragma unroll
+  for (int j = 0; j < kMaxModuli; ++j) {
+    const double s1 = T.s1[j], s2 = T.s2[j];  // zero beyond nmod
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+      const double y = (double)(int8_t)(w[j] >> (8 * t));
+      c1[t] = fma(s1, y, c1[t]);
+      c2[t] = fma(s2, y, c2[t]);
+    }
+  }
+  const int en = P.eb[n] - P.kshift;
+  const int64_t noff = (int64_t)(n / P.rdiv) * P.sn1 + (int64_t)(n % P.rdiv) * P.sn0;
+#pragma unroll
+  for (int t = 0; t < 4; ++t) {
+    const int m = 4 * q + t;
+    if (m >= P.M) break;
+    const double qq = rint((c1[t] + c2[t]) * T.inv_M);
+    const double cint = fma(-qq, T.M1, c1[t]) + fma(-qq, T.M2, c2[t]);
+    const double val = P.alpha * ldexp(cint, P.ea[m] + en);
+    const int64_t off = (int64_t)(m / P.rdiv) * P.sm1 + (int64_t)(m % P.rdiv) * P.sm0 + noff;
+    if (P.accumulate) P.C[off] += val; else P.C[off] = val;
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -265,9 +288,21 @@ __global__ void __launch_bounds__(256) k_to_residues(const ResidueBatch b, const
   const int tid = threadIdx.x;
   const double *src = J.src + (int64_t)row * J.ld;
   double mx = 0.0;
-  for (int k = tid; k < J.K; k += 256) {
-    const double x = src[k];
-    res_row[k] = x;
+  // four loads in flight per thread
+  int k0 = tid;
+  for (; k0 + 3 * 256 < J.K; k0 += 4 * 256) {
+    double x[4];
+#pragma unroll
+    for (int t = 0; t < 4; ++t) x[t] = src[k0 + t * 256];
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+      res_row[k0 + t * 256] = x[t];
+      mx = fmax(mx, fabs(x[t]));
+    }
+  }
+  for (; k0 < J.K; k0 += 256) {
+    const double x = src[k0];
+    res_row[k0] = x;
     mx = fmax(mx, fabs(x));
   }
   for (int o = 32; o > 0; o >>= 1) mx = fmax(mx, __shfl_xor(mx, o));
@@ -412,10 +447,12 @@ hipError_t gemm_crt_launch(GemmBatch &b, const CrtTable &T, hipStream_t s) {
   }
   b.total_tiles = total;
   if (total == 0) return hipSuccess;
-  // each XCD's contiguous range holds an equal share of every problem
+  // per-modulus logical order: the c-th eighth of every product, c = 0 .. 7
+  ModSched sched{};
   b.nseg = 0;
   int start = 0;
-  for (int c = 0; c < kGemmXcds; ++c)
+  for (int c = 0; c < kGemmXcds; ++c) {
+    sched.xs[c] = start;
     for (int q = 0; q < b.count; ++q) {
       const int n = b.p[q].tiles_m * b.p[q].tiles_n;
       const int lo = (int)((int64_t)n * c / kGemmXcds), hi = (int)((int64_t)n * (c + 1) / kGemmXcds);
@@ -426,9 +463,20 @@ hipError_t gemm_crt_launch(GemmBatch &b, const CrtTable &T, hipStream_t s) {
       ++b.nseg;
       start += hi - lo;
     }
+  }
+  sched.xs[kGemmXcds] = start;
   b.seg_start[b.nseg] = start;
-  hipLaunchKernelGGL(gemm_crt_kernel, dim3(total), dim3(kNT), 0, s, b, T);
+  int share = 0;
+  for (int c = 0; c < kGemmXcds; ++c) share = std::max(share, sched.xs[c + 1] - sched.xs[c]);
+  hipLaunchKernelGGL(gemm_mod_kernel, dim3(kGemmXcds * share * T.nmod), dim3(kNT), 0, s, b, T, sched);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  int64_t most = 0;
+  for (int q = 0; q < b.count; ++q) most = std::max(most, (int64_t)((b.p[q].M + 3) / 4) * b.p[q].N);
+  hipLaunchKernelGGL(k_crt_combine, dim3((unsigned)((most + 255) / 256), b.count), dim3(256), 0, s, b, T);
   return hipGetLastError();
 }
+
+int64_t crt_residue_out_bytes(int M, int N) { return (int64_t)round_up(M, 4) * N; }
 
 }  // namespace acse
