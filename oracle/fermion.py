@@ -214,6 +214,16 @@ def singlet_blocks_from_state(fock, psi):
     return g1[a, a].copy(), 0.5 * g2[a, a, a, a], 0.5 * g2[a, b, a, b]
 
 
+def spin_blocks_from_state(fock, psi):
+    """(gamma_a, gamma_b, 2D_aa, 2D_bb, 2D_ab) of a state of any S_z."""
+    r = fock.n // 2
+    g1 = fock.rdm1(psi)
+    g2 = fock.rdm2(psi)
+    a, b = slice(0, r), slice(r, 2 * r)
+    return (g1[a, a].copy(), g1[b, b].copy(), 0.5 * g2[a, a, a, a], 0.5 * g2[b, b, b, b],
+            0.5 * g2[a, b, a, b])
+
+
 def fci_singlet_problem(h, V, N):
     """Lowest singlet of the Hamiltonian of Eq. (1) built from spatial (h, V):
     returns dict(energy, psi, fock, gamma, d2aa, d2ab)."""

@@ -82,6 +82,40 @@ def spin_orbital_to_blocks(t4):
     return t4[a, a, a, a].copy(), t4[a, b, a, b].copy()
 
 
+def spin_blocks_to_spin_orbital(ga, gb, d2aa, d2bb, d2ab):
+    """Spin-orbital (1D, 2D) of a state of any S_z from its unique spin blocks
+    (the fixed-spin blocks named in the Theory section: alpha-alpha,
+    beta-beta and alpha-beta):
+      1D(pa|ra) = ga, 1D(pb|rb) = gb;
+      2D(pa qa|ra sa) = d2aa, 2D(pb qb|rb sb) = d2bb, 2D(pa qb|ra sb) = d2ab;
+    the three other mixed blocks follow from the fermionic antisymmetry of
+    each index pair alone: 2D(pb qa|rb sa) = d2ab[q,p,s,r],
+    2D(pa qb|rb sa) = -d2ab[p,q,s,r], 2D(pb qa|ra sb) = -d2ab[q,p,r,s].
+    With gb = ga and d2bb = d2aa (and d2ab invariant under (pq)(rs) ->
+    (qp)(sr)) this is the singlet lift above."""
+    r = ga.shape[0]
+    n = 2 * r
+    a, b = spin_blocks(r)
+    d1 = np.zeros((n, n))
+    d1[a, a] = ga
+    d1[b, b] = gb
+    d2 = np.zeros((n, n, n, n))
+    d2[a, a, a, a] = d2aa
+    d2[b, b, b, b] = d2bb
+    d2[a, b, a, b] = d2ab
+    d2[b, a, b, a] = d2ab.transpose(1, 0, 3, 2)
+    d2[a, b, b, a] = -d2ab.transpose(0, 1, 3, 2)
+    d2[b, a, a, b] = -d2ab.transpose(1, 0, 2, 3)
+    return d1, d2
+
+
+def spin_orbital_to_spin_blocks(t4):
+    """(alpha-alpha, beta-beta, alpha-beta) spatial blocks of a spin-orbital 4-index tensor."""
+    r = t4.shape[0] // 2
+    a, b = spin_blocks(r)
+    return t4[a, a, a, a].copy(), t4[b, b, b, b].copy(), t4[a, b, a, b].copy()
+
+
 def block_traces(d2aa, d2ab):
     """Tr 2D_aa and Tr 2D_ab (App. A: N_a(N_a-1)/2 and N_a N_b/2)."""
     r = d2aa.shape[0]

@@ -38,15 +38,24 @@ def active_mask(active, r):
     return ~all4
 
 
+def _trace(d2):
+    r = d2.shape[0]
+    return float(sum(d2[p, q, p, q] for p in range(r) for q in range(r)))
+
+
+def restore_block_traces(blocks, traces):
+    """Trace restoration after the update: each 2-RDM spin block is multiplied
+    by the ratio of the trace it must keep (its input trace, App. A) to the
+    trace it has now, so every block trace returns to its input value and
+    nothing else changes shape.  Returns the rescaled blocks and the factors."""
+    scales = tuple(t0 / _trace(b) for b, t0 in zip(blocks, traces))
+    return tuple(b * c for b, c in zip(blocks, scales)), scales
+
+
 def restore_traces(d2aa, d2ab, traces):
-    """Trace restoration after the update: each block is multiplied by the ratio
-    of the trace it must keep (``traces`` = (Tr 2D_aa, Tr 2D_ab) of the input
-    state, App. A) to the trace it has now, so Tr 2D_aa and Tr 2D_ab return to
-    their input values and nothing else changes shape.  Returns the rescaled
-    blocks and the two factors."""
-    t1aa, t1ab = rdm.block_traces(d2aa, d2ab)
-    s_aa, s_ab = traces[0] / t1aa, traces[1] / t1ab
-    return d2aa * s_aa, d2ab * s_ab, (s_aa, s_ab)
+    """restore_block_traces for the two stored singlet blocks (aa, ab)."""
+    (aa, ab), scales = restore_block_traces((d2aa, d2ab), traces)
+    return aa, ab, scales
 
 
 def norm2_spin_orbital(t4):
@@ -96,6 +105,56 @@ def step(h, V, N, gamma, d2aa, d2ab, eps, active=None, keep_spin_orbital=False, 
                d2aa=d2aa_1, d2ab=d2ab_1, gamma=gamma_1, energy=e1,
                energy0=float(np.sum(K * d2)),
                trace_scale=scale)
+    if keep_spin_orbital:
+        out.update(R=R, U=U, Rm=Rm, K=K, d1=d1, d2=d2)
+    return out
+
+
+# ---------------------------------------------------------------------------
+# States of any S_z (N_alpha != N_beta): the three unique spin blocks
+# ---------------------------------------------------------------------------
+
+def energy_spin(h, V, Na, Nb, d2aa, d2bb, d2ab):
+    """E = Tr(K 2D) over spin orbitals (Eq. (2) with Eq. (6))."""
+    r = h.shape[0]
+    K = rdm.reduced_hamiltonian(h, V, Na + Nb)
+    _, d2 = rdm.spin_blocks_to_spin_orbital(np.eye(r), np.eye(r), d2aa, d2bb, d2ab)
+    return float(np.sum(K * d2))
+
+
+def residual_spin(h, V, Na, Nb, ga, gb, d2aa, d2bb, d2ab):
+    """R = F(K) (Eq. (4)) of a state of any S_z; returns (R_aa, R_bb, R_ab,
+    ||R||^2 over spin orbitals)."""
+    K = rdm.reduced_hamiltonian(h, V, Na + Nb)
+    d1, d2 = rdm.spin_blocks_to_spin_orbital(ga, gb, d2aa, d2bb, d2ab)
+    R = residual_map(K, d1, d2, hermitian=True).numpy()
+    raa, rbb, rab = rdm.spin_orbital_to_spin_blocks(R)
+    return raa, rbb, rab, norm2_spin_orbital(R)
+
+
+def step_spin(h, V, Na, Nb, ga, gb, d2aa, d2bb, d2ab, eps, active=None, keep_spin_orbital=False):
+    """One Euler step (Eq. (9)) of a state of any S_z, with the readings of
+    ``step`` (mask, trace restoration per spin block, 1-RDM contraction); the
+    1-RDM blocks after the step are those of the contraction of the new 2-RDM."""
+    r = h.shape[0]
+    N = Na + Nb
+    K = rdm.reduced_hamiltonian(h, V, N)
+    d1, d2 = rdm.spin_blocks_to_spin_orbital(ga, gb, d2aa, d2bb, d2ab)
+    R = residual_map(K, d1, d2, hermitian=True).numpy()
+    n2 = norm2_spin_orbital(R)
+    mask = active_mask(active, r)
+    Rm = R if mask is None else R * mask
+    U = residual_map(Rm, d1, d2, hermitian=False).numpy()
+    raa, rbb, rab = rdm.spin_orbital_to_spin_blocks(R)
+    uaa, ubb, uab = rdm.spin_orbital_to_spin_blocks(U)
+    traces = tuple(_trace(b) for b in (d2aa, d2bb, d2ab))
+    (aa1, bb1, ab1), scale = restore_block_traces((d2aa + eps * uaa, d2bb + eps * ubb, d2ab + eps * uab), traces)
+    _, d2_1 = rdm.spin_blocks_to_spin_orbital(ga, gb, aa1, bb1, ab1)
+    g1 = rdm.contract_to_1rdm(d2_1, N)
+    a, b = rdm.spin_blocks(r)
+    out = dict(R_aa=raa, R_bb=rbb, R_ab=rab, norm2=n2, U_aa=uaa, U_bb=ubb, U_ab=uab,
+               d2aa=aa1, d2bb=bb1, d2ab=ab1, gamma_a=g1[a, a].copy(), gamma_b=g1[b, b].copy(),
+               energy=float(np.sum(K * d2_1)), energy0=float(np.sum(K * d2)), trace_scale=scale)
     if keep_spin_orbital:
         out.update(R=R, U=U, Rm=Rm, K=K, d1=d1, d2=d2)
     return out

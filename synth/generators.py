@@ -15,6 +15,15 @@ h diagonal, h upper triangle, Cholesky vectors, orbital rotation, cumulant):
   symmetry, Delta_aa = Delta_ab - Delta_ab(r<->s) (singlet-consistent), then one
   global scale so the spin-orbital trace 2 Tr 2D_aa + 2 Tr 2D_ab = N(N-1)/2.
 
+States of any S_z (``spin_problem``, N_alpha != N_beta): per spin sigma the
+occupations n_i = 0.01 + 0.98 / (1 + exp((i - mu)/0.5)) bisected to sum N_sigma
+(all zero for N_sigma = 0, all one for N_sigma = r); gamma_sigma = U_sigma
+diag(n_sigma) U_sigma^T with its own Haar rotation (drawn alpha then beta);
+2D_ss = 1/2 (g_pr g_qs - g_ps g_qr) + c Delta_ss (Delta antisymmetric in each
+pair and Hermitian, drawn aa then bb), 2D_ab = 1/2 ga_pr gb_qs + c Delta_ab
+(Delta Hermitian only, drawn last); each block then scaled to its App. A trace
+N_a(N_a-1)/2, N_b(N_b-1)/2, N_a N_b / 2.
+
 These stand in for the molecular 1-/2-RDMs and integrals of the paper's
 CASSCF-referenced runs (sizes r = 12 ... 116 spatial orbitals), which are not
 available here.
@@ -150,3 +159,53 @@ def symmetric_direction(rng, r, scale=1.0):
 def cotangent(rng, r):
     """A seeded Gaussian cotangent (Rbar_aa, Rbar_ab) on the residual blocks."""
     return rng.normal(size=(r, r, r, r)), rng.normal(size=(r, r, r, r))
+
+
+def _spin_occupations(r, Ns):
+    if Ns == 0:
+        return np.zeros(r)
+    if Ns >= r:
+        return np.ones(r)
+    idx = np.arange(r, dtype=np.float64)
+    occ = lambda mu: 0.01 + 0.98 / (1.0 + np.exp((idx - mu) / 0.5))
+    lo, hi = -50.0, r + 50.0
+    for _ in range(200):
+        mu = 0.5 * (lo + hi)
+        if occ(mu).sum() < Ns:
+            lo = mu
+        else:
+            hi = mu
+    return occ(0.5 * (lo + hi))
+
+
+def _scaled(block, target):
+    tr = np.einsum('pqpq->', block)
+    return block * (target / tr) if target != 0.0 else np.zeros_like(block)
+
+
+def spin_problem(r, Na, Nb, n_chol, seed=0, cumulant_scale=1e-2):
+    """(h, V, gamma_a, gamma_b, d2aa, d2bb, d2ab) of one synthetic state with
+    N_a alpha and N_b beta electrons (any S_z)."""
+    rng = np.random.default_rng(seed)
+    h, V = hamiltonian(rng, r, n_chol)
+    g = []
+    for Ns in (Na, Nb):
+        U = haar_orthogonal(rng, r)
+        gs = (U * _spin_occupations(r, Ns)) @ U.T
+        g.append(0.5 * (gs + gs.T))
+    ga, gb = g
+    blocks = []
+    for gs in (ga, gb):
+        x = rng.normal(size=(r, r, r, r))
+        x = x - x.transpose(1, 0, 2, 3)
+        x = x - x.transpose(0, 1, 3, 2)
+        x = 0.125 * (x + x.transpose(2, 3, 0, 1))
+        mf = 0.5 * (np.einsum('pr,qs->pqrs', gs, gs) - np.einsum('ps,qr->pqrs', gs, gs))
+        blocks.append(mf + cumulant_scale * x)
+    x = rng.normal(size=(r, r, r, r))
+    dab = 0.5 * np.einsum('pr,qs->pqrs', ga, gb) + cumulant_scale * 0.5 * (x + x.transpose(2, 3, 0, 1))
+    d2aa = _scaled(blocks[0], Na * (Na - 1) / 2.0)
+    d2bb = _scaled(blocks[1], Nb * (Nb - 1) / 2.0)
+    d2ab = _scaled(dab, Na * Nb / 2.0)
+    return dict(r=r, Na=Na, Nb=Nb, N=Na + Nb, h=h, V=V, gamma_a=ga, gamma_b=gb, d2aa=d2aa, d2bb=d2bb,
+                d2ab=d2ab)
