@@ -47,8 +47,10 @@ def restore_block_traces(blocks, traces):
     """Trace restoration after the update: each 2-RDM spin block is multiplied
     by the ratio of the trace it must keep (its input trace, App. A) to the
     trace it has now, so every block trace returns to its input value and
-    nothing else changes shape.  Returns the rescaled blocks and the factors."""
-    scales = tuple(t0 / _trace(b) for b, t0 in zip(blocks, traces))
+    nothing else changes shape.  A block whose input trace is zero (fewer than
+    two electrons of that pair kind: the block of the exact state vanishes) is
+    set to zero.  Returns the rescaled blocks and the factors."""
+    scales = tuple((t0 / _trace(b)) if t0 != 0.0 else 0.0 for b, t0 in zip(blocks, traces))
     return tuple(b * c for b, c in zip(blocks, scales)), scales
 
 

@@ -92,7 +92,7 @@ def test_residual_spin_for_open_shell_determinants(r, Na, Nb):
     assert abs(n2 - np.sum(brute ** 2)) < 1e-12 * np.sum(brute ** 2)
 
 
-@pytest.mark.parametrize("r,Na,Nb", [(3, 2, 1), (4, 3, 1)])
+@pytest.mark.parametrize("r,Na,Nb", [(3, 2, 1), (4, 3, 1), (4, 3, 0)])
 def test_update_spin_for_open_shell_determinants(r, Na, Nb):
     """The update blocks of one step equal 1/2 <[O, A]> with A = sum R a+a+aa in
     Fock space (exact 3-RDM of a determinant), and E1 - E0 = -eps ||R||^2 to
@@ -170,3 +170,21 @@ def test_spin_lift_planted_mistakes_fail():
     for wrong in (wrong_sign, beta_from_alpha):
         _, l2 = wrong(ga, gb, aa, bb, ab)
         assert np.abs(l2 - d2).max() > 1e-3, wrong.__name__
+
+
+@pytest.mark.parametrize("Na,Nb", [(3, 0), (4, 1)])
+def test_step_spin_blocks_of_fewer_than_two_electrons_stay_zero(Na, Nb):
+    """A pair kind with fewer than two electrons has a zero block in every
+    N-representable 2-RDM (its App. A trace is zero): the step keeps it zero,
+    and the other blocks keep their traces."""
+    p = gen.spin_problem(5, Na, Nb, 10, seed=7)
+    args = (p["h"], p["V"], p["Na"], p["Nb"], p["gamma_a"], p["gamma_b"], p["d2aa"], p["d2bb"], p["d2ab"])
+    assert not np.any(p["d2bb"]) and (Nb > 0) == bool(np.any(p["d2ab"]))
+    o = st.step_spin(*args, 1e-3)
+    assert not np.any(o["d2bb"])
+    if Nb == 0:
+        assert not np.any(o["d2ab"]) and not np.any(o["gamma_b"])
+    tr = lambda x: np.einsum('pqpq->', x)
+    for k in ("d2aa", "d2ab"):
+        assert abs(tr(o[k]) - tr(p[k])) < 1e-13 * max(1.0, abs(tr(p[k])))
+    assert np.all(np.isfinite(o["d2aa"])) and np.isfinite(o["energy"])
