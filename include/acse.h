@@ -70,7 +70,8 @@ typedef enum {
   ACSE_ERR_ARG = 1,         /* null pointer, bad enum value, non-finite eps */
   ACSE_ERR_SHAPE = 2,       /* r < 2, r > r_max, N < 2 or N > 2r */
   ACSE_ERR_ALIGN = 3,       /* a device pointer is not 16-byte aligned */
-  ACSE_ERR_UNSUPPORTED = 4, /* n_alpha != n_beta (non-singlet blocks), feature not built */
+  ACSE_ERR_UNSUPPORTED = 4, /* n_alpha != n_beta in the singlet calls (use the _spin calls),
+                               a combination of options that is not built */
   ACSE_ERR_NOMEM = 5,       /* workspace allocation failed */
   ACSE_ERR_HIP = 6,         /* a HIP runtime call failed */
   ACSE_ERR_NONFINITE = 7    /* ||R||^2 or E came out non-finite */
@@ -405,6 +406,59 @@ acse_status acse_autotune_batched(acse_ctx ctx, int32_t count, const acse_proble
  * enqueued and acse_last_error(NULL) gives the detail (per host thread). */
 acse_status acse_residual_noalloc(void *hip_stream, const acse_problem *prob, const acse_options *opts,
                                   double *R_aa, double *R_ab, double *norm2_dev);
+
+/* States of any S_z (N_alpha != N_beta; the Theory section's fixed-spin
+ * blocks): the three unique 2-RDM blocks and one 1-RDM per spin.
+ *   d1a, d1b   device [r*r]  1D(pa|ra), 1D(pb|rb)
+ *   d2aa, d2bb device [r^4]  2D(pa qa|ra sa), 2D(pb qb|rb sb), antisymmetric in
+ *              each pair and Hermitian (App. A traces N_a(N_a-1)/2, N_b(N_b-1)/2)
+ *   d2ab       device [r^4]  2D(pa qb|ra sb), Hermitian (trace N_a N_b / 2); no
+ *              pair-exchange symmetry is assumed.  The other mixed blocks follow
+ *              from the antisymmetry: 2D(pb qa|rb sa) = d2ab[q,p,s,r],
+ *              2D(pa qb|rb sa) = -d2ab[p,q,s,r].
+ * The residual and update come in the same three blocks (R_aa, R_bb, R_ab with
+ * R_ab = R(ia jb|ka lb)); ||R||^2 = ||R_aa||^2 + ||R_bb||^2 + 4 ||R_ab||^2 over
+ * spin orbitals.  These calls run the spin-orbital map (Valdemoro 3-RDM) over
+ * spatial spin blocks: 17 r^2 x r^2 x r^2 FP64 products per map.  Options:
+ * precision ACSE_FP64 only, Valdemoro only, ACSE_FLAG_GENERAL_KERNELS allowed
+ * (ACSE_FLAG_CHECK_INPUTS and the other precisions are ACSE_ERR_UNSUPPORTED);
+ * tile as for acse_residual.  The first call allocates a workspace for r_max:
+ * 48 r_max^4 doubles and 25 GEMM operand buffers (about 3.7 GB at
+ * r_max = 50), kept until acse_destroy.  A singlet state given in this form
+ * (d1b = d1a, d2bb = d2aa, d2ab pair-exchange symmetric) gives the singlet
+ * calls' results. */
+typedef struct {
+  int32_t r;          /* spatial orbitals, 2 <= r <= r_max */
+  int32_t n_alpha;    /* alpha electrons, <= r */
+  int32_t n_beta;     /* beta electrons, <= r; n_alpha + n_beta >= 2 */
+  const double *h;    /* device [r*r] */
+  const double *V;    /* device [r^4] */
+  double *d1a;        /* device [r*r] (acse_step_spin overwrites it) */
+  double *d1b;        /* device [r*r] (acse_step_spin overwrites it) */
+  double *d2aa;       /* device [r^4] (acse_step_spin overwrites it) */
+  double *d2bb;       /* device [r^4] (acse_step_spin overwrites it) */
+  double *d2ab;       /* device [r^4] (acse_step_spin overwrites it) */
+} acse_problem_spin;
+
+/* Residual of Eq. (4) for a state of any S_z: R_aa, R_bb, R_ab (device [r^4]
+ * each) and, if norm2_host is not NULL, ||R||^2 (synchronises). */
+acse_status acse_residual_spin(acse_ctx ctx, const acse_problem_spin *prob, const acse_options *opts,
+                               double *R_aa, double *R_bb, double *R_ab, double *norm2_host);
+
+/* One Euler step of Eq. (9) for a state of any S_z: R, R_m = mask(R),
+ * U = F(R_m), each 2-RDM block <- (block + eps U) rescaled to its input trace
+ * (a block with zero input trace, i.e. fewer than two electrons of its kind, is
+ * set to zero),
+ * 1D per spin <- 2/(N-1) times the partial trace of the new 2-RDM (alpha:
+ * Tr_2 d2aa + Tr_2 d2ab; beta: Tr_2 d2bb + Tr_1 d2ab), E of the new 2-RDM.
+ * Outputs as for acse_step (NULL output arrays are allowed). */
+acse_status acse_step_spin(acse_ctx ctx, acse_problem_spin *prob, double eps, const acse_options *opts,
+                           double *R_aa, double *R_bb, double *R_ab, double *U_aa, double *U_bb, double *U_ab,
+                           double *E_host, double *norm2_host);
+
+/* Energy Tr(K 2D) = <K_s, d2aa> + <K_s, d2bb> + 2 <K_s, d2ab> (Eq. (2), Eq. (6)); the
+ * 1-RDM pointers may be NULL.  Synchronises. */
+acse_status acse_energy_spin(acse_ctx ctx, const acse_problem_spin *prob, double *E_host);
 
 /* Human-readable name of a status code (static storage). */
 const char *acse_status_str(acse_status s);

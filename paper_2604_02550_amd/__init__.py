@@ -33,7 +33,8 @@ EXPORTS = ("acse_create", "acse_destroy", "acse_set_stream", "acse_residual", "a
            "acse_energy", "acse_step", "acse_status_str", "acse_last_error",
            "acse_workspace_bytes", "acse_profile_enable", "acse_profile_read", "acse_autotune",
            "acse_residual_vjp", "acse_energy_vjp", "acse_residual_batched",
-           "acse_autotune_batched", "acse_solve", "acse_residual_noalloc")
+           "acse_autotune_batched", "acse_solve", "acse_residual_noalloc", "acse_residual_spin",
+           "acse_step_spin", "acse_energy_spin")
 NUM_TILE_CONFIGS = 3
 NUM_STAGES = 8
 STAGES = ("rdm_operands", "fold", "transforms", "gemm", "assembly", "step_tail", "ny_share", "ny_gemm")
@@ -43,6 +44,13 @@ class Problem(ctypes.Structure):
     _fields_ = [("r", ctypes.c_int32), ("n_alpha", ctypes.c_int32), ("n_beta", ctypes.c_int32),
                 ("h", ctypes.c_void_p), ("V", ctypes.c_void_p), ("d1", ctypes.c_void_p),
                 ("d2aa", ctypes.c_void_p), ("d2ab", ctypes.c_void_p)]
+
+
+class ProblemSpin(ctypes.Structure):
+    """acse_problem_spin: a state of any S_z (alpha and beta 1-RDMs, the three 2-RDM blocks)."""
+    _fields_ = [("r", ctypes.c_int32), ("n_alpha", ctypes.c_int32), ("n_beta", ctypes.c_int32),
+                ("h", ctypes.c_void_p), ("V", ctypes.c_void_p), ("d1a", ctypes.c_void_p), ("d1b", ctypes.c_void_p),
+                ("d2aa", ctypes.c_void_p), ("d2bb", ctypes.c_void_p), ("d2ab", ctypes.c_void_p)]
 
 
 class ProfileData(ctypes.Structure):
@@ -115,6 +123,11 @@ _sig = {
                                              _D]),
     "acse_residual_noalloc": (ctypes.c_int, [_P, ctypes.POINTER(Problem), ctypes.POINTER(Options), _P, _P,
                                              _P]),
+    "acse_residual_spin": (ctypes.c_int, [_P, ctypes.POINTER(ProblemSpin), ctypes.POINTER(Options), _P, _P, _P,
+                                          _D]),
+    "acse_step_spin": (ctypes.c_int, [_P, ctypes.POINTER(ProblemSpin), ctypes.c_double, ctypes.POINTER(Options),
+                                      _P, _P, _P, _P, _P, _P, _D, _D]),
+    "acse_energy_spin": (ctypes.c_int, [_P, ctypes.POINTER(ProblemSpin), _D]),
     "acse_solve": (ctypes.c_int, [_P, ctypes.POINTER(Problem), ctypes.POINTER(Options),
                                   ctypes.POINTER(SolveOptions), ctypes.POINTER(SolveResult),
                                   ctypes.POINTER(Trial), ctypes.c_int32]),
@@ -440,6 +453,72 @@ class Context:
             return dict(d1=d1, d2aa=d2aa, d2ab=d2ab, iterations=done, trajectory=traj, stop="max_iter",
                         resumed=resumed)
         return dict(out, iterations=done, trajectory=traj, resumed=resumed)
+
+    # ----- states of any S_z (N_alpha != N_beta) --------------------------------
+    def problem_spin(self, h, V, d1a, d1b, d2aa, d2bb, d2ab, n_alpha, n_beta):
+        """Device copies and the ctypes struct of a state of any S_z."""
+        r = check_problem_shapes(h, V, d1a, d2aa, d2ab)
+        if _shape(d1b) != (r, r):
+            raise ValueError(f"d1b must have shape ({r}, {r}), got {_shape(d1b)}")
+        if _numel(d2bb) != r ** 4:
+            raise ValueError(f"d2bb must hold r^4 = {r ** 4} elements (r = {r}), got shape {_shape(d2bb)}")
+        t = [_dev(x, self.device) for x in (h, V, d1a, d1b, d2aa, d2bb, d2ab)]
+        prob = ProblemSpin(r, int(n_alpha), int(n_beta), *[x.data_ptr() for x in t])
+        return prob, t
+
+    def residual_spin_raw(self, prob, opts, R_aa, R_bb, R_ab, want_norm=True):
+        _check_opts(opts, prob.r)
+        for name, x in (("R_aa", R_aa), ("R_bb", R_bb), ("R_ab", R_ab)):
+            _check_dev4(x, prob.r, name, self.device)
+        n2 = ctypes.c_double(0.0)
+        self._check(_lib.acse_residual_spin(self._h, ctypes.byref(prob), ctypes.byref(opts), _ptr(R_aa), _ptr(R_bb),
+                                            _ptr(R_ab), ctypes.byref(n2) if want_norm else None))
+        return n2.value
+
+    def residual_spin(self, h, V, d1a, d1b, d2aa, d2bb, d2ab, n_alpha, n_beta, tile=-1, flags=0):
+        """R_aa, R_bb, R_ab (device) and ||R||^2 of Eq. (4) for a state of any S_z."""
+        prob, keep = self.problem_spin(h, V, d1a, d1b, d2aa, d2bb, d2ab, n_alpha, n_beta)
+        r = prob.r
+        R = [torch.empty((r, r, r, r), dtype=torch.float64, device=self.device) for _ in range(3)]
+        n2 = self.residual_spin_raw(prob, self.options("fp64", None, tile, flags), *R)
+        return R[0], R[1], R[2], n2
+
+    def step_spin_raw(self, prob, eps, opts, outs=(None,) * 6, want=True):
+        _check_opts(opts, prob.r)
+        for name, x in zip(("R_aa", "R_bb", "R_ab", "U_aa", "U_bb", "U_ab"), outs):
+            if x is not None:
+                _check_dev4(x, prob.r, name, self.device)
+        e = ctypes.c_double(0.0)
+        n2 = ctypes.c_double(0.0)
+        self._check(_lib.acse_step_spin(self._h, ctypes.byref(prob), float(eps), ctypes.byref(opts),
+                                        *[_ptr(x) for x in outs], ctypes.byref(e) if want else None,
+                                        ctypes.byref(n2) if want else None))
+        return e.value, n2.value
+
+    def step_spin(self, h, V, d1a, d1b, d2aa, d2bb, d2ab, n_alpha, n_beta, eps=1e-3, active=None, tile=-1,
+                  return_ru=False, flags=0):
+        """One Euler step of Eq. (9) for a state of any S_z on device copies; a dict
+        with the new d1a, d1b, d2aa, d2bb, d2ab, the energy after the step and
+        ||R||^2 before it (and R, U blocks with return_ru)."""
+        prob, t = self.problem_spin(h, V, d1a, d1b, d2aa, d2bb, d2ab, n_alpha, n_beta)
+        r = prob.r
+        outs = [None] * 6
+        if return_ru:
+            outs = [torch.empty((r, r, r, r), dtype=torch.float64, device=self.device) for _ in range(6)]
+        E, n2 = self.step_spin_raw(prob, eps, self.options("fp64", active, tile, flags), outs)
+        res = dict(d1a=t[2], d1b=t[3], d2aa=t[4], d2bb=t[5], d2ab=t[6], energy=E, norm2=n2)
+        if return_ru:
+            res.update(zip(("R_aa", "R_bb", "R_ab", "U_aa", "U_bb", "U_ab"), outs))
+        return res
+
+    def energy_spin(self, h, V, d2aa, d2bb, d2ab, n_alpha, n_beta):
+        """E = Tr(K 2D) for a state of any S_z."""
+        r = _shape(h)[0]
+        z = torch.zeros(r, r, dtype=torch.float64)
+        prob, keep = self.problem_spin(h, V, z, z, d2aa, d2bb, d2ab, n_alpha, n_beta)
+        e = ctypes.c_double(0.0)
+        self._check(_lib.acse_energy_spin(self._h, ctypes.byref(prob), ctypes.byref(e)))
+        return e.value
 
     def residual_vjp_raw(self, prob, opts, Rbar_aa, Rbar_ab, h_bar, V_bar, d1_bar, d2aa_bar, d2ab_bar):
         _check_opts(opts, prob.r)

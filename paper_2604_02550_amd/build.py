@@ -8,7 +8,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 OBJ = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libacse.so")
-SOURCES = ["acse_api.hip", "gemm.hip", "gemm_crt.hip", "ny.hip", "tensor_ops.hip", "vjp.hip"]
+SOURCES = ["acse_api.hip", "gemm.hip", "gemm_crt.hip", "ny.hip", "spin.hip", "tensor_ops.hip", "vjp.hip"]
 HIPCC_FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
     # no packed FP32 instructions in generated code

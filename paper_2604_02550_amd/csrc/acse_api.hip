@@ -122,6 +122,10 @@ struct acse_ctx_s {
   int8_t *cy = nullptr;    // residues of the six products (all moduli)
   CrtTable crt{};
   int crt_moduli = 0;      // modulus count of the call in progress (set by validate)
+  // spin-block path for states of any S_z (allocated by its first call, for r_max)
+  void *spbase = nullptr;
+  int64_t spbytes = 0;
+  void *spws = nullptr;    // its array table (a SpinWs)
 };
 
 namespace {
@@ -248,7 +252,7 @@ acse_status validate(acse_ctx c, const acse_problem *p, const acse_options *o, b
   if (p->n_alpha < 0 || p->n_beta < 0 || N < 2 || p->n_alpha > p->r || p->n_beta > p->r)
     return fail(c, ACSE_ERR_SHAPE, "electron counts must satisfy N >= 2 and n_sigma <= r");
   if (p->n_alpha != p->n_beta)
-    return fail(c, ACSE_ERR_UNSUPPORTED, "only n_alpha == n_beta (singlet blocks) is built");
+    return fail(c, ACSE_ERR_UNSUPPORTED, "n_alpha != n_beta: this call takes singlet blocks (use the _spin calls)");
   if (!p->h || !p->V || !p->d2aa || !p->d2ab || (need_d1 && !p->d1))
     return fail(c, ACSE_ERR_ARG, "a problem pointer is NULL");
   if (!aligned16(p->h) || !aligned16(p->V) || !aligned16(p->d2aa) || !aligned16(p->d2ab) ||
@@ -870,6 +874,7 @@ int keep_default(int best_cfg, double best_ms, int default_cfg, const double *ti
 }
 
 const char *last_noctx_error();
+void release_spin_ws(acse_ctx c);
 
 acse_status fetch_scalars(acse_ctx c, double *norm2_host, double *E_host) {
   if (!norm2_host && !E_host) return ACSE_OK;
@@ -976,6 +981,8 @@ acse_status acse_destroy(acse_ctx ctx) {
   if (ctx->sbase) (void)hipFree(ctx->sbase);
   if (ctx->nybase) (void)hipFree(ctx->nybase);
   if (ctx->cbase) (void)hipFree(ctx->cbase);
+  if (ctx->spbase) (void)hipFree(ctx->spbase);
+  release_spin_ws(ctx);
   if (ctx->bbase) (void)hipFree(ctx->bbase);
   if (ctx->hdesc) (void)hipHostFree(ctx->hdesc);
   if (ctx->hdesc_done) (void)hipEventDestroy(ctx->hdesc_done);
@@ -2286,3 +2293,471 @@ extern "C" acse_status acse_autotune_batched(acse_ctx ctx, int32_t count, const 
   *best_tile = arg;
   return ACSE_OK;
 }
+
+// ===========================================================================
+// States of any S_z (N_alpha != N_beta): the three unique spin blocks
+// (alpha-alpha, beta-beta, alpha-beta) and one 1-RDM per spin.
+//
+// The map F(X) runs over spin-orbital tensors held as spatial spin blocks
+// (block b: bit 3 - t set when index t is beta).  With X_A the
+// pair-antisymmetrised X, W = Gamma2 - 2/3 Gamma1^Gamma1 and Gamma1 =
+// diag(ga, gb):
+//   Y^{ij}_{kl} = sum_rs Gamma2^{ij}_{rs} X_A^{kl}_{rs}
+//   H^{kl}_{rs} = sum_p X_A^{kp}_{rs} Gamma1_pl,   f_ks = sum_r H^{kr}_{rs}
+//   t_jk = sum_prs W^{jp}_{rs} X_A^{kp}_{rs},      Xt^{kp}_{is} = sum_r Gamma1_ir X_A^{kp}_{rs}
+//   E^{ij}_{kl} = 2 sum_ps Xt^{kp}_{is} W^{jp}_{sl}
+//   T = sum_rs W^{ij}_{rs} H^{kl}_{rs} + 2 sum_s f_ks W^{ij}_{sl} + Gamma1_il t_jk
+//       - Gamma1_jl t_ik + E^{ij}_{kl} - E^{ji}_{kl}
+//   S = Y - (T - T(k<->l)),   F = S - S^T (Hermitian X) or S + S^T (anti-Hermitian X)
+// (the Valdemoro 3-RDM of App. C folded in as in the singlet path).  Only the
+// blocks that reach F's alpha-alpha, beta-beta and alpha-beta outputs are
+// formed; a summed pair antisymmetric in both operands with opposite spins is
+// taken once with weight 2.  17 r^2 x r^2 x r^2 FP64 products per map (Y 3,
+// the W H products 4, E 10), grouped in three launches.
+// ===========================================================================
+#include "spin.h"
+
+namespace {
+
+constexpr int kSpinNat = 48;   // natural r^4 arrays
+constexpr int kSpinOps = 25;   // GEMM operand buffers
+enum { B0000 = 0, B0101 = 5, B0110 = 6, B1001 = 9, B1010 = 10, B1111 = 15 };
+constexpr int kSix[6] = {B0000, B1111, B0101, B1010, B0110, B1001};
+inline int spin_of(int b, int t) { return (b >> (3 - t)) & 1; }
+
+struct SpinWs {
+  double *XA[16] = {}, *H[16] = {}, *Xt[16] = {}, *W[16] = {}, *Y[16] = {}, *T[16] = {}, *E[16] = {}, *S[16] = {};
+  double *R[3] = {}, *U[3] = {}, *Rm[3] = {};
+  double *G2p[16] = {}, *Wp[16] = {}, *WPp[16] = {}, *XAp[16] = {}, *Hp[16] = {}, *XtP[16] = {};
+  double *f[2] = {}, *t[2] = {}, *part = nullptr, *scal = nullptr;
+};
+
+acse_status ensure_spin_ws(acse_ctx c, SpinWs *&out) {
+  if (c->spws) { out = static_cast<SpinWs *>(c->spws); return ACSE_OK; }
+  const int rm = c->r_max;
+  const int64_t r2 = (int64_t)rm * rm;
+  const int64_t nat = round_up(r2 * r2 * 8, 256);
+  const int64_t opb = round_up(op_rows(rm) * op_ld(rm) * 8, 256);
+  const int64_t small = round_up((4 * r2 + (int64_t)t_partial_blocks() * r2 + kDotBlocks + 64) * 8, 256);
+  const int64_t bytes = kSpinNat * nat + kSpinOps * opb + small;
+  if (hipMalloc(&c->spbase, bytes) != hipSuccess) {
+    (void)hipGetLastError();
+    c->spbase = nullptr;
+    return fail(c, ACSE_ERR_NOMEM, "cannot allocate the spin-block workspace (" + std::to_string(bytes) + " bytes)");
+  }
+  c->spbytes = bytes;
+  // operand padding rows are read by full tiles: give every byte a defined value once
+  if (launch_fill((kSpinOps * opb) / 8, 0.0, reinterpret_cast<double *>(static_cast<char *>(c->spbase) + kSpinNat * nat),
+                  c->stream) != hipSuccess)
+    return fail(c, ACSE_ERR_HIP, "spin workspace fill failed");
+  SpinWs w;
+  char *q = static_cast<char *>(c->spbase);
+  auto take_nat = [&]() { double *x = reinterpret_cast<double *>(q); q += nat; return x; };
+  for (int b : kSix) { w.XA[b] = take_nat(); w.Xt[b] = take_nat(); w.W[b] = take_nat(); w.E[b] = take_nat(); }
+  for (int b : {B0000, B1111, B0101, B1001, B0110}) w.H[b] = take_nat();
+  for (int b : {B0000, B1111, B0101}) { w.Y[b] = take_nat(); w.S[b] = take_nat(); }
+  for (int b : {B0000, B1111, B0101, B0110}) w.T[b] = take_nat();
+  for (int k = 0; k < 3; ++k) { w.R[k] = take_nat(); w.U[k] = take_nat(); w.Rm[k] = take_nat(); }
+  auto take_op = [&]() { double *x = reinterpret_cast<double *>(q); q += opb; return x; };
+  for (int b : {B0000, B1111, B0101}) { w.G2p[b] = take_op(); w.Wp[b] = take_op(); w.XAp[b] = take_op(); }
+  for (int b : kSix) { w.WPp[b] = take_op(); w.XtP[b] = take_op(); }
+  for (int b : {B0000, B1111, B0101, B1001}) w.Hp[b] = take_op();
+  double *sm = reinterpret_cast<double *>(q);
+  w.f[0] = sm; w.f[1] = sm + r2; w.t[0] = sm + 2 * r2; w.t[1] = sm + 3 * r2;
+  w.part = sm + 4 * r2;
+  w.scal = w.part + (int64_t)t_partial_blocks() * r2 + kDotBlocks;
+  SpinWs *keep = new (std::nothrow) SpinWs(w);
+  if (!keep) return fail(c, ACSE_ERR_NOMEM, "cannot allocate the spin workspace table");
+  c->spws = keep;
+  out = keep;
+  return ACSE_OK;
+}
+
+acse_status validate_spin(acse_ctx c, const acse_problem_spin *p, const acse_options *o, bool need_d1) {
+  if (!c) return ACSE_ERR_ARG;
+  if (!p) return fail(c, ACSE_ERR_ARG, "problem is NULL");
+  if (p->r < 2 || p->r > c->r_max)
+    return fail(c, ACSE_ERR_SHAPE, "r = " + std::to_string(p->r) + " outside [2, r_max = " +
+                                       std::to_string(c->r_max) + "]");
+  const int N = p->n_alpha + p->n_beta;
+  if (p->n_alpha < 0 || p->n_beta < 0 || N < 2 || p->n_alpha > p->r || p->n_beta > p->r)
+    return fail(c, ACSE_ERR_SHAPE, "electron counts must satisfy N >= 2 and n_sigma <= r");
+  const void *ptrs[7] = {p->h, p->V, p->d2aa, p->d2bb, p->d2ab, p->d1a, p->d1b};
+  for (int k = 0; k < (need_d1 ? 7 : 5); ++k) {
+    if (!ptrs[k]) return fail(c, ACSE_ERR_ARG, "a problem pointer is NULL");
+    if (!aligned16(ptrs[k])) return fail(c, ACSE_ERR_ALIGN, "problem arrays must be 16-byte aligned");
+  }
+  if (o) {
+    if (o->precision != ACSE_FP64)
+      return fail(c, ACSE_ERR_UNSUPPORTED, "the spin-block path runs its products in FP64 only");
+    if (o->reconstruction != ACSE_RECON_V)
+      return fail(c, ACSE_ERR_UNSUPPORTED, "the spin-block path takes the Valdemoro reconstruction only");
+    if (o->flags & ~ACSE_FLAG_GENERAL_KERNELS)
+      return fail(c, (o->flags & ~(ACSE_FLAG_GENERAL_KERNELS | ACSE_FLAG_CHECK_INPUTS)) ? ACSE_ERR_ARG
+                                                                                         : ACSE_ERR_UNSUPPORTED,
+                  "the spin-block path accepts ACSE_FLAG_GENERAL_KERNELS only");
+    if (o->tile < -1 || o->tile >= gemm_num_tiles(GEMM_F64)) return fail(c, ACSE_ERR_ARG, "tile configuration out of range");
+  }
+  c->general = o && (o->flags & ACSE_FLAG_GENERAL_KERNELS);
+  c->ny_on = false;
+  c->crt_moduli = 0;
+  return ACSE_OK;
+}
+
+// W (natural, six blocks) and the RDM-side GEMM operands of a step.
+acse_status spin_prep(acse_ctx c, SpinWs &w, const acse_problem_spin *p) {
+  const int r = p->r;
+  const int ld = (int)op_ld(r);
+  hipStream_t s = c->stream;
+  StageTimer timer(c, 0);
+  const double *ga = p->d1a, *gb = p->d1b;
+  auto comb1 = [&](double *out, const double *in, double coef, int f0, int f1, int f2, int f3) {
+    Terms4 T{};
+    T.n = 1;
+    T.t[0] = term4(in, coef, r, f0, f1, f2, f3);
+    return launch_combine4(r, T, out, 0, nullptr, s);
+  };
+  const double c23 = 2.0 / 3.0;
+  // W = Gamma2 - 2/3 (g_pr g_qs - g_ps g_qr) per block
+  HIP_TRY(c, comb1(w.W[B0000], p->d2aa, 2.0, 0, 1, 2, 3));
+  HIP_TRY(c, launch_outer4(r, -c23, ga, 0, 2, ga, 1, 3, w.W[B0000], s));
+  HIP_TRY(c, launch_outer4(r, c23, ga, 0, 3, ga, 1, 2, w.W[B0000], s));
+  HIP_TRY(c, comb1(w.W[B1111], p->d2bb, 2.0, 0, 1, 2, 3));
+  HIP_TRY(c, launch_outer4(r, -c23, gb, 0, 2, gb, 1, 3, w.W[B1111], s));
+  HIP_TRY(c, launch_outer4(r, c23, gb, 0, 3, gb, 1, 2, w.W[B1111], s));
+  HIP_TRY(c, comb1(w.W[B0101], p->d2ab, 2.0, 0, 1, 2, 3));                 // 2D(pa qb|ra sb)
+  HIP_TRY(c, launch_outer4(r, -c23, ga, 0, 2, gb, 1, 3, w.W[B0101], s));
+  HIP_TRY(c, comb1(w.W[B1010], p->d2ab, 2.0, 1, 0, 3, 2));                 // 2D(pb qa|rb sa) = d2ab[q,p,s,r]
+  HIP_TRY(c, launch_outer4(r, -c23, gb, 0, 2, ga, 1, 3, w.W[B1010], s));
+  HIP_TRY(c, comb1(w.W[B0110], p->d2ab, -2.0, 0, 1, 3, 2));                // 2D(pa qb|rb sa) = -d2ab[p,q,s,r]
+  HIP_TRY(c, launch_outer4(r, c23, ga, 0, 3, gb, 1, 2, w.W[B0110], s));
+  HIP_TRY(c, comb1(w.W[B1001], p->d2ab, -2.0, 1, 0, 2, 3));                // 2D(pb qa|ra sb) = -d2ab[q,p,r,s]
+  HIP_TRY(c, launch_outer4(r, c23, gb, 0, 3, ga, 1, 2, w.W[B1001], s));
+  // operands: Gamma2 and W blocks as [(ij)][(rs)], W blocks as [(jl)][(ps)] from W[j,p,s,l]
+  auto pack1 = [&](double *out, const double *in, double coef, int f0, int f1, int f2, int f3) {
+    Terms4 T{};
+    T.n = 1;
+    T.t[0] = term4(in, coef, r, f0, f1, f2, f3);
+    return launch_pack_op4(r, T, out, ld, s);
+  };
+  HIP_TRY(c, pack1(w.G2p[B0000], p->d2aa, 2.0, 0, 1, 2, 3));
+  HIP_TRY(c, pack1(w.G2p[B1111], p->d2bb, 2.0, 0, 1, 2, 3));
+  HIP_TRY(c, pack1(w.G2p[B0101], p->d2ab, 2.0, 0, 1, 2, 3));
+  for (int b : {B0000, B1111, B0101}) HIP_TRY(c, pack1(w.Wp[b], w.W[b], 1.0, 0, 1, 2, 3));
+  for (int b : kSix) HIP_TRY(c, pack1(w.WPp[b], w.W[b], 1.0, 0, 3, 1, 2));
+  return ACSE_OK;
+}
+
+// X_A blocks of the residual (X = K): alpha-alpha and beta-beta blocks A_aa,
+// the (ab|ab) blocks A_ab = K_s / 2, the (ab|ba) blocks -A_ab with the lower pair exchanged.
+acse_status spin_xa_from_fold(acse_ctx c, SpinWs &w, int r) {
+  hipStream_t s = c->stream;
+  auto comb1 = [&](double *out, const double *in, double coef, int f0, int f1, int f2, int f3) {
+    Terms4 T{};
+    T.n = 1;
+    T.t[0] = term4(in, coef, r, f0, f1, f2, f3);
+    return launch_combine4(r, T, out, 0, nullptr, s);
+  };
+  const double *Aaa = c->ws.Aaa, *Aab = c->ws.Aab;
+  HIP_TRY(c, comb1(w.XA[B0000], Aaa, 1.0, 0, 1, 2, 3));
+  HIP_TRY(c, comb1(w.XA[B1111], Aaa, 1.0, 0, 1, 2, 3));
+  HIP_TRY(c, comb1(w.XA[B0101], Aab, 1.0, 0, 1, 2, 3));
+  HIP_TRY(c, comb1(w.XA[B1010], Aab, 1.0, 0, 1, 2, 3));
+  HIP_TRY(c, comb1(w.XA[B0110], Aab, -1.0, 0, 1, 3, 2));
+  HIP_TRY(c, comb1(w.XA[B1001], Aab, -1.0, 0, 1, 3, 2));
+  return ACSE_OK;
+}
+
+// X_A blocks of an antisymmetric X given by its three unique blocks.
+acse_status spin_xa_from_blocks(acse_ctx c, SpinWs &w, int r, const double *Xaa, const double *Xbb,
+                                const double *Xab) {
+  hipStream_t s = c->stream;
+  auto comb1 = [&](double *out, const double *in, double coef, int f0, int f1, int f2, int f3) {
+    Terms4 T{};
+    T.n = 1;
+    T.t[0] = term4(in, coef, r, f0, f1, f2, f3);
+    return launch_combine4(r, T, out, 0, nullptr, s);
+  };
+  HIP_TRY(c, comb1(w.XA[B0000], Xaa, 1.0, 0, 1, 2, 3));
+  HIP_TRY(c, comb1(w.XA[B1111], Xbb, 1.0, 0, 1, 2, 3));
+  HIP_TRY(c, comb1(w.XA[B0101], Xab, 1.0, 0, 1, 2, 3));
+  HIP_TRY(c, comb1(w.XA[B1010], Xab, 1.0, 1, 0, 3, 2));
+  HIP_TRY(c, comb1(w.XA[B0110], Xab, -1.0, 0, 1, 3, 2));
+  HIP_TRY(c, comb1(w.XA[B1001], Xab, -1.0, 1, 0, 2, 3));
+  return ACSE_OK;
+}
+
+// F(X) for the X_A blocks in the workspace into O[0..2] = (aa, bb, ab);
+// sigma = -1 Hermitian X, +1 anti-Hermitian.  If Rm is not null it receives
+// the masked copy.  The squared block norms land in w.scal[slot .. slot+2].
+acse_status spin_map(acse_ctx c, SpinWs &w, int r, const double *ga, const double *gb, double sigma,
+                     double *const *O, const ActiveBits *mask, double *const *Rm, int slot) {
+  const int64_t r2 = (int64_t)r * r, r3 = r2 * r;
+  const int ld = (int)op_ld(r);
+  hipStream_t s = c->stream;
+  const double *g[2] = {ga, gb};
+  {
+    StageTimer t2(c, 2);
+    // H = X_A x_1 Gamma1 (index 1 keeps its spin)
+    for (int b : {B0000, B1111, B0101, B1001, B0110}) {
+      ModeArgs m = mode_base(c, r, g[spin_of(b, 1)]);
+      m.A = r; m.Bn = r2; m.in1 = w.XA[b]; m.transpose_m = 1;
+      m.so1 = r3; m.so0 = 0; m.sx = r2; m.sb = 1; m.out_cols_fast = 1;
+      HIP_TRY(c, launch_mode(GEMM_F64, m, OperandRef{w.H[b], nullptr}, s));
+    }
+    // f_ks = sum_r H^{kr}_{rs} per spin
+    HIP_TRY(c, launch_trace12(r, w.H[B0000], w.f[0], 0, s));
+    HIP_TRY(c, launch_trace12(r, w.H[B0110], w.f[0], 1, s));
+    HIP_TRY(c, launch_trace12(r, w.H[B1111], w.f[1], 0, s));
+    HIP_TRY(c, launch_trace12(r, w.H[B1001], w.f[1], 1, s));
+    // t_jk per spin: Gram products over (p, r, s)
+    HIP_TRY(c, launch_gram(r, w.W[B0000], w.XA[B0000], 1.0, w.W[B0101], w.XA[B0101], 1.0, w.part, w.t[0], 0, s,
+                           c->general));
+    HIP_TRY(c, launch_gram(r, w.W[B0110], w.XA[B0110], 1.0, w.W[B0110], w.XA[B0110], 0.0, w.part, w.t[0], 1, s,
+                           c->general));
+    HIP_TRY(c, launch_gram(r, w.W[B1111], w.XA[B1111], 1.0, w.W[B1010], w.XA[B1010], 1.0, w.part, w.t[1], 0, s,
+                           c->general));
+    HIP_TRY(c, launch_gram(r, w.W[B1001], w.XA[B1001], 1.0, w.W[B1001], w.XA[B1001], 0.0, w.part, w.t[1], 1, s,
+                           c->general));
+    // Xt = Gamma1 x_2 X_A (index 2 keeps its spin)
+    for (int b : kSix) {
+      ModeArgs m = mode_base(c, r, g[spin_of(b, 2)]);
+      m.A = r2; m.Bn = r; m.in1 = w.XA[b];
+      m.so1 = r2; m.so0 = 0; m.sx = r; m.sb = 1; m.out_cols_fast = 1;
+      HIP_TRY(c, launch_mode(GEMM_F64, m, OperandRef{w.Xt[b], nullptr}, s));
+    }
+    // X-side operands
+    auto pack1 = [&](double *out, const double *in, int f0, int f1, int f2, int f3) {
+      Terms4 T{};
+      T.n = 1;
+      T.t[0] = term4(in, 1.0, r, f0, f1, f2, f3);
+      return launch_pack_op4(r, T, out, ld, s);
+    };
+    for (int b : {B0000, B1111, B0101}) HIP_TRY(c, pack1(w.XAp[b], w.XA[b], 0, 1, 2, 3));
+    for (int b : {B0000, B1111, B0101, B1001}) HIP_TRY(c, pack1(w.Hp[b], w.H[b], 0, 1, 2, 3));
+    for (int b : kSix) HIP_TRY(c, pack1(w.XtP[b], w.Xt[b], 0, 2, 1, 3));  // rows (k,i), K (p,s)
+  }
+  // the 17 products
+  {
+    StageTimer t3(c, 3);
+    const int kp = gemm_kp(GEMM_F64, (int)r2, ld);
+    auto prob = [&](GemmProb &P, const double *A, const double *B, double alpha, double *C, bool ph, int acc) {
+      P = GemmProb{};
+      P.A = A; P.B = B; P.C = C; P.alpha = alpha;
+      P.M = (int)r2; P.N = (int)r2; P.Kp = kp; P.ld = ld; P.rdiv = r;
+      if (ph) { P.sm1 = r; P.sm0 = r3; P.sn1 = r2; P.sn0 = 1; }      // rows (k,i), cols (j,l) -> [i,j,k,l]
+      else { P.sm1 = r3; P.sm0 = r2; P.sn1 = r; P.sn0 = 1; }         // natural [(ij)][(kl)]
+      P.ksplit = 1; P.kchunk = kp; P.accumulate = acc;
+    };
+    const int cfg = map_cfg(c, GEMM_F64, r, -1);
+    GemmBatch b1{};
+    b1.count = 7;
+    prob(b1.p[0], w.G2p[B0000], w.XAp[B0000], 1.0, w.Y[B0000], false, 0);
+    prob(b1.p[1], w.G2p[B1111], w.XAp[B1111], 1.0, w.Y[B1111], false, 0);
+    prob(b1.p[2], w.G2p[B0101], w.XAp[B0101], 2.0, w.Y[B0101], false, 0);
+    prob(b1.p[3], w.Wp[B0000], w.Hp[B0000], 1.0, w.T[B0000], false, 0);
+    prob(b1.p[4], w.Wp[B1111], w.Hp[B1111], 1.0, w.T[B1111], false, 0);
+    prob(b1.p[5], w.Wp[B0101], w.Hp[B0101], 2.0, w.T[B0101], false, 0);
+    prob(b1.p[6], w.Wp[B0101], w.Hp[B1001], 2.0, w.T[B0110], false, 0);
+    HIP_TRY(c, gemm_launch(GEMM_F64, cfg, b1, s));
+    // E^{ij}_{kl} = 2 sum Xt^{kp}_{is} W^{jp}_{sl}: first terms, then the second ones
+    GemmBatch b2{};
+    b2.count = 6;
+    prob(b2.p[0], w.XtP[B0000], w.WPp[B0000], 2.0, w.E[B0000], true, 0);
+    prob(b2.p[1], w.XtP[B1111], w.WPp[B1111], 2.0, w.E[B1111], true, 0);
+    prob(b2.p[2], w.XtP[B0000], w.WPp[B1001], 2.0, w.E[B0101], true, 0);
+    prob(b2.p[3], w.XtP[B0110], w.WPp[B0101], 2.0, w.E[B1001], true, 0);
+    prob(b2.p[4], w.XtP[B1001], w.WPp[B1010], 2.0, w.E[B0110], true, 0);
+    prob(b2.p[5], w.XtP[B1010], w.WPp[B0000], 2.0, w.E[B1010], true, 0);
+    HIP_TRY(c, gemm_launch(GEMM_F64, cfg, b2, s));
+    GemmBatch b3{};
+    b3.count = 4;
+    prob(b3.p[0], w.XtP[B0101], w.WPp[B0110], 2.0, w.E[B0000], true, 1);
+    prob(b3.p[1], w.XtP[B1010], w.WPp[B1001], 2.0, w.E[B1111], true, 1);
+    prob(b3.p[2], w.XtP[B0101], w.WPp[B1111], 2.0, w.E[B0101], true, 1);
+    prob(b3.p[3], w.XtP[B1111], w.WPp[B0110], 2.0, w.E[B1010], true, 1);
+    HIP_TRY(c, gemm_launch(GEMM_F64, cfg, b3, s));
+  }
+  StageTimer t4(c, 4);
+  // T += 2 sum_s f_ks W^{ij}_{sl} (index 2 of W keeps its spin)
+  for (int b : {B0000, B1111, B0101, B0110}) {
+    ModeArgs m = mode_base(c, r, w.f[spin_of(b, 2)]);
+    m.A = r2; m.Bn = r; m.in1 = w.W[b]; m.alpha = 2.0; m.accumulate = 1;
+    m.so1 = r2; m.so0 = 0; m.sx = r; m.sb = 1; m.out_cols_fast = 1;
+    HIP_TRY(c, launch_mode(GEMM_F64, m, OperandRef{w.T[b], nullptr}, s));
+  }
+  // T += Gamma1_il t_jk - Gamma1_jl t_ik
+  HIP_TRY(c, launch_outer4(r, 1.0, ga, 0, 3, w.t[0], 1, 2, w.T[B0000], s));
+  HIP_TRY(c, launch_outer4(r, -1.0, ga, 1, 3, w.t[0], 0, 2, w.T[B0000], s));
+  HIP_TRY(c, launch_outer4(r, 1.0, gb, 0, 3, w.t[1], 1, 2, w.T[B1111], s));
+  HIP_TRY(c, launch_outer4(r, -1.0, gb, 1, 3, w.t[1], 0, 2, w.T[B1111], s));
+  HIP_TRY(c, launch_outer4(r, -1.0, gb, 1, 3, w.t[0], 0, 2, w.T[B0101], s));
+  HIP_TRY(c, launch_outer4(r, 1.0, ga, 0, 3, w.t[1], 1, 2, w.T[B0110], s));
+  // S = Y - C, C = T' - T'(k<->l), T' = T + E - E(i<->j)
+  struct Sel { int b, bl, bi, bli; };  // block, its k<->l partner, i<->j of each
+  const Sel sel[3] = {{B0000, B0000, B0000, B0000}, {B1111, B1111, B1111, B1111}, {B0101, B0110, B1001, B1010}};
+  const int out_blocks[3] = {B0000, B1111, B0101};
+  for (int q = 0; q < 3; ++q) {
+    const Sel &x = sel[q];
+    Terms4 T{};
+    T.n = 7;
+    T.t[0] = term4(w.Y[x.b], 1.0, r, 0, 1, 2, 3);
+    T.t[1] = term4(w.T[x.b], -1.0, r, 0, 1, 2, 3);
+    T.t[2] = term4(w.E[x.b], -1.0, r, 0, 1, 2, 3);
+    T.t[3] = term4(w.E[x.bi], 1.0, r, 1, 0, 2, 3);
+    T.t[4] = term4(w.T[x.bl], 1.0, r, 0, 1, 3, 2);
+    T.t[5] = term4(w.E[x.bl], 1.0, r, 0, 1, 3, 2);
+    T.t[6] = term4(w.E[x.bli], -1.0, r, 1, 0, 3, 2);
+    HIP_TRY(c, launch_combine4(r, T, w.S[out_blocks[q]], 0, nullptr, s));
+  }
+  // F = S + sigma S^T, the masked copy, the block norms
+  for (int q = 0; q < 3; ++q) {
+    const int b = out_blocks[q];
+    Terms4 T{};
+    T.n = 2;
+    T.t[0] = term4(w.S[b], 1.0, r, 0, 1, 2, 3);
+    T.t[1] = term4(w.S[b], sigma, r, 2, 3, 0, 1);
+    HIP_TRY(c, launch_combine4(r, T, O[q], 0, nullptr, s));
+    if (Rm) {
+      Terms4 M{};
+      M.n = 1;
+      M.t[0] = term4(O[q], 1.0, r, 0, 1, 2, 3);
+      HIP_TRY(c, launch_combine4(r, M, Rm[q], 0, mask, s));
+    }
+    HIP_TRY(c, launch_dot(r2 * r2, O[q], O[q], w.part, w.scal + slot + q, s));
+  }
+  return ACSE_OK;
+}
+
+// Host copies of n scalars from w.scal (synchronises).
+acse_status spin_fetch(acse_ctx c, SpinWs &w, double *host, int n) {
+  HIP_TRY(c, hipMemcpyAsync(host, w.scal, n * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+  HIP_TRY(c, hipStreamSynchronize(c->stream));
+  return ACSE_OK;
+}
+
+acse_status spin_energy(acse_ctx c, SpinWs &w, const acse_problem_spin *p, int slot) {
+  // E = <K_s, d2aa> + <K_s, d2bb> + 2 <K_s, d2ab>, K_s = 2 A_ab (the fold's unantisymmetrised half)
+  const int64_t n4 = (int64_t)p->r * p->r * p->r * p->r;
+  HIP_TRY(c, launch_dot(n4, c->ws.Aab, p->d2aa, w.part, w.scal + slot, c->stream));
+  HIP_TRY(c, launch_dot(n4, c->ws.Aab, p->d2bb, w.part, w.scal + slot + 1, c->stream));
+  HIP_TRY(c, launch_dot(n4, c->ws.Aab, p->d2ab, w.part, w.scal + slot + 2, c->stream));
+  return ACSE_OK;
+}
+
+acse_status spin_check_outputs(acse_ctx c, std::initializer_list<const void *> outs) {
+  for (const void *q : outs)
+    if (q && !aligned16(q)) return fail(c, ACSE_ERR_ALIGN, "output arrays must be 16-byte aligned");
+  return ACSE_OK;
+}
+
+}  // namespace
+
+extern "C" acse_status acse_energy_spin(acse_ctx ctx, const acse_problem_spin *prob, double *E_host) {
+  acse_status st = validate_spin(ctx, prob, nullptr, false);
+  if (st != ACSE_OK) return st;
+  if (!E_host) return fail(ctx, ACSE_ERR_ARG, "E_host is NULL");
+  HIP_TRY(ctx, hipSetDevice(ctx->device));
+  SpinWs *w = nullptr;
+  if ((st = ensure_spin_ws(ctx, w)) != ACSE_OK) return st;
+  HIP_TRY(ctx, launch_fold(prob->r, prob->n_alpha + prob->n_beta, prob->h, prob->V, ctx->ws.Aaa, ctx->ws.Aab,
+                           ctx->stream));
+  if ((st = spin_energy(ctx, *w, prob, 0)) != ACSE_OK) return st;
+  double e[3];
+  if ((st = spin_fetch(ctx, *w, e, 3)) != ACSE_OK) return st;
+  *E_host = 2.0 * (e[0] + e[1]) + 4.0 * e[2];
+  if (!std::isfinite(*E_host)) return fail(ctx, ACSE_ERR_NONFINITE, "energy is not finite");
+  return ACSE_OK;
+}
+
+extern "C" acse_status acse_residual_spin(acse_ctx ctx, const acse_problem_spin *prob, const acse_options *opts,
+                                          double *R_aa, double *R_bb, double *R_ab, double *norm2_host) {
+  acse_status st = validate_spin(ctx, prob, opts, true);
+  if (st != ACSE_OK) return st;
+  for (auto q : {std::make_pair((const void *)R_aa, "R_aa"), std::make_pair((const void *)R_bb, "R_bb"),
+                 std::make_pair((const void *)R_ab, "R_ab")})
+    if ((st = check_out(ctx, q.first, q.second)) != ACSE_OK) return st;
+  HIP_TRY(ctx, hipSetDevice(ctx->device));
+  SpinWs *w = nullptr;
+  if ((st = ensure_spin_ws(ctx, w)) != ACSE_OK) return st;
+  const int r = prob->r;
+  if ((st = spin_prep(ctx, *w, prob)) != ACSE_OK) return st;
+  {
+    StageTimer t1(ctx, 1);
+    HIP_TRY(ctx, launch_fold(r, prob->n_alpha + prob->n_beta, prob->h, prob->V, ctx->ws.Aaa, ctx->ws.Aab,
+                             ctx->stream));
+  }
+  if ((st = spin_xa_from_fold(ctx, *w, r)) != ACSE_OK) return st;
+  double *O[3] = {R_aa, R_bb, R_ab};
+  if ((st = spin_map(ctx, *w, r, prob->d1a, prob->d1b, -1.0, O, nullptr, nullptr, 0)) != ACSE_OK) return st;
+  if (!norm2_host) return ACSE_OK;
+  double n[3];
+  if ((st = spin_fetch(ctx, *w, n, 3)) != ACSE_OK) return st;
+  *norm2_host = n[0] + n[1] + 4.0 * n[2];
+  if (!std::isfinite(*norm2_host)) return fail(ctx, ACSE_ERR_NONFINITE, "||R||^2 is not finite");
+  return ACSE_OK;
+}
+
+extern "C" acse_status acse_step_spin(acse_ctx ctx, acse_problem_spin *prob, double eps, const acse_options *opts,
+                                      double *R_aa, double *R_bb, double *R_ab, double *U_aa, double *U_bb,
+                                      double *U_ab, double *E_host, double *norm2_host) {
+  acse_status st = validate_spin(ctx, prob, opts, true);
+  if (st != ACSE_OK) return st;
+  if (!std::isfinite(eps)) return fail(ctx, ACSE_ERR_ARG, "eps is not finite");
+  if ((st = spin_check_outputs(ctx, {R_aa, R_bb, R_ab, U_aa, U_bb, U_ab})) != ACSE_OK) return st;
+  HIP_TRY(ctx, hipSetDevice(ctx->device));
+  SpinWs *w = nullptr;
+  if ((st = ensure_spin_ws(ctx, w)) != ACSE_OK) return st;
+  const int r = prob->r;
+  const int N = prob->n_alpha + prob->n_beta;
+  hipStream_t s = ctx->stream;
+  double *R[3] = {R_aa ? R_aa : w->R[0], R_bb ? R_bb : w->R[1], R_ab ? R_ab : w->R[2]};
+  double *U[3] = {U_aa ? U_aa : w->U[0], U_bb ? U_bb : w->U[1], U_ab ? U_ab : w->U[2]};
+  bool masked = false;
+  const ActiveBits act = make_bits(opts, r, &masked);
+  if ((st = spin_prep(ctx, *w, prob)) != ACSE_OK) return st;
+  {
+    StageTimer t1(ctx, 1);
+    HIP_TRY(ctx, launch_fold(r, N, prob->h, prob->V, ctx->ws.Aaa, ctx->ws.Aab, s));
+  }
+  if ((st = spin_xa_from_fold(ctx, *w, r)) != ACSE_OK) return st;
+  // R = F(K), block norms -> scal[0..2], masked copy
+  if ((st = spin_map(ctx, *w, r, prob->d1a, prob->d1b, -1.0, R, masked ? &act : nullptr, masked ? w->Rm : nullptr,
+                     0)) != ACSE_OK)
+    return st;
+  // U = F(R_m) on the same 2-RDM
+  const double *const *Xm = masked ? w->Rm : R;
+  if ((st = spin_xa_from_blocks(ctx, *w, r, Xm[0], Xm[1], Xm[2])) != ACSE_OK) return st;
+  if ((st = spin_map(ctx, *w, r, prob->d1a, prob->d1b, 1.0, U, nullptr, nullptr, 3)) != ACSE_OK) return st;
+  // 2D <- (2D + eps U) per block at its input trace; 1-RDM per spin; energy
+  {
+    StageTimer t5(ctx, 5);
+    const double *tr_in[6] = {prob->d2aa, prob->d2bb, prob->d2ab, U[0], U[1], U[2]};
+    double *traces = w->scal + 16;
+    HIP_TRY(ctx, launch_pair_traces(r, 6, tr_in, traces, s));
+    double *d2[3] = {prob->d2aa, prob->d2bb, prob->d2ab};
+    const double *Uc[3] = {U[0], U[1], U[2]};
+    HIP_TRY(ctx, launch_spin_update(r, eps, d2, Uc, traces, s));
+    HIP_TRY(ctx, launch_spin_1rdm(r, N, prob->d2aa, prob->d2bb, prob->d2ab, prob->d1a, prob->d1b, s));
+    if ((st = spin_energy(ctx, *w, prob, 6)) != ACSE_OK) return st;
+  }
+  if (!E_host && !norm2_host) return ACSE_OK;
+  double v[9];
+  if ((st = spin_fetch(ctx, *w, v, 9)) != ACSE_OK) return st;
+  if (norm2_host) {
+    *norm2_host = v[0] + v[1] + 4.0 * v[2];
+    if (!std::isfinite(*norm2_host)) return fail(ctx, ACSE_ERR_NONFINITE, "||R||^2 is not finite");
+  }
+  if (E_host) {
+    *E_host = 2.0 * (v[6] + v[7]) + 4.0 * v[8];
+    if (!std::isfinite(*E_host)) return fail(ctx, ACSE_ERR_NONFINITE, "energy is not finite");
+  }
+  return ACSE_OK;
+}
+
+namespace {
+void release_spin_ws(acse_ctx c) {
+  delete static_cast<SpinWs *>(c->spws);
+  c->spws = nullptr;
+}
+}  // namespace

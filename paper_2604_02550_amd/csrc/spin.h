@@ -1,0 +1,52 @@
+// Kernels of the residual map for states of any S_z (spin.hip): generic
+// O(r^4) passes over spatial spin blocks (natural r^4 arrays [i][j][k][l]).
+#pragma once
+#include "acse_internal.h"
+#include "tensor_ops.h"
+
+namespace acse {
+
+// One term of a linear combination: c * in[i s0 + j s1 + k s2 + l s3].
+struct Term4 {
+  const double *in;
+  double c;
+  int64_t s[4];
+};
+constexpr int kMaxTerms4 = 8;
+struct Terms4 {
+  Term4 t[kMaxTerms4];
+  int n;
+};
+// Strides of a natural r^4 array read with its indices permuted: term index
+// position d of the output reads source index position from[d].
+inline Term4 term4(const double *in, double c, int r, int f0, int f1, int f2, int f3) {
+  const int64_t nat[4] = {(int64_t)r * r * r, (int64_t)r * r, r, 1};
+  return Term4{in, c, {nat[f0], nat[f1], nat[f2], nat[f3]}};
+}
+
+// out[i,j,k,l] (+)= sum_t c_t in_t[...]; with `mask` set, elements whose four
+// spatial indices are all active are written as zero.
+hipError_t launch_combine4(int r, const Terms4 &terms, double *out, int accumulate, const ActiveBits *mask,
+                           hipStream_t s);
+// GEMM operand [rows r^2][ld] with row (a,b), column (c,d) = sum_t c_t in_t[...]
+// and the columns r^2 .. ld-1 zero.
+hipError_t launch_pack_op4(int r, const Terms4 &terms, double *out, int ld, hipStream_t s);
+// out[i,j,k,l] += c A[x_a0, x_a1] B[x_b0, x_b1], x = (i,j,k,l) and a0..b1
+// positions in it (A, B r x r).
+hipError_t launch_outer4(int r, double c, const double *A, int a0, int a1, const double *B, int b0, int b1,
+                         double *out, hipStream_t s);
+// out[k,s] (+)= sum_r in[k,r,r,s].
+hipError_t launch_trace12(int r, const double *in, double *out, int accumulate, hipStream_t s);
+// traces[q] = sum_{p,q'} in_q[p,q',p,q'] for q < count (count <= 8).
+hipError_t launch_pair_traces(int r, int count, const double *const *in, double *traces, hipStream_t s);
+// Step tail per spin block q < 3: d_q <- (d_q + eps U_q) tr0_q / (tr0_q + eps trU_q)
+// with tr0 = traces[q], trU = traces[3 + q] (the trace of a sum is the sum of
+// the traces).
+hipError_t launch_spin_update(int r, double eps, double *const *d2, const double *const *U, const double *traces,
+                              hipStream_t s);
+// 1-RDM per spin from the new 2-RDM blocks: ga = c (Tr_2 d2aa + Tr_2 d2ab),
+// gb = c (Tr_2 d2bb + Tr_1 d2ab), c = 2 / (N - 1).
+hipError_t launch_spin_1rdm(int r, int N, const double *d2aa, const double *d2bb, const double *d2ab, double *ga,
+                            double *gb, hipStream_t s);
+
+}  // namespace acse

@@ -1,0 +1,179 @@
+// Generic O(r^4) kernels of the general-spin residual map: linear
+// combinations of index-permuted spin blocks, GEMM operand packing, outer
+// products of two-index tensors, partial traces and the per-block step tail.
+// The O(r^6) work of the map runs on the grouped MFMA GEMM and the O(r^5)
+// one-index transforms on the mode-product kernel (tensor_ops.hip).
+#include "spin.h"
+
+namespace acse {
+
+namespace {
+
+__device__ inline bool all_active(const ActiveBits &m, int i, int j, int k, int l) {
+  auto on = [&](int q) { return (m.w[q >> 6] >> (q & 63)) & 1ull; };
+  return on(i) && on(j) && on(k) && on(l);
+}
+
+// One thread per output element; the output is written in its natural order
+// (coalesced), the terms are read through their strides.
+__global__ void __launch_bounds__(256)
+k_combine4(int r, const Terms4 T, double *__restrict__ out, int accumulate, int masked, const ActiveBits mask) {
+  const int64_t n = (int64_t)r * r * r * r;
+  const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (e >= n) return;
+  const int l = (int)(e % r), k = (int)((e / r) % r), j = (int)((e / ((int64_t)r * r)) % r),
+            i = (int)(e / ((int64_t)r * r * r));
+  double v = 0.0;
+  for (int t = 0; t < T.n; ++t) {
+    const Term4 &q = T.t[t];
+    v += q.c * q.in[i * q.s[0] + j * q.s[1] + k * q.s[2] + l * q.s[3]];
+  }
+  if (accumulate) v += out[e];
+  if (masked && all_active(mask, i, j, k, l)) v = 0.0;
+  out[e] = v;
+}
+
+__global__ void __launch_bounds__(256) k_pack_op4(int r, const Terms4 T, double *__restrict__ out, int ld) {
+  const int64_t r2 = (int64_t)r * r;
+  const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (e >= r2 * ld) return;
+  const int64_t row = e / ld, col = e - row * ld;
+  double v = 0.0;
+  if (col < r2) {
+    const int i = (int)(row / r), j = (int)(row % r), k = (int)(col / r), l = (int)(col % r);
+    for (int t = 0; t < T.n; ++t) {
+      const Term4 &q = T.t[t];
+      v += q.c * q.in[i * q.s[0] + j * q.s[1] + k * q.s[2] + l * q.s[3]];
+    }
+  }
+  out[e] = v;
+}
+
+__global__ void __launch_bounds__(256)
+k_outer4(int r, double c, const double *__restrict__ A, int a0, int a1, const double *__restrict__ B, int b0, int b1,
+         double *__restrict__ out) {
+  const int64_t n = (int64_t)r * r * r * r;
+  const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (e >= n) return;
+  int x[4];
+  x[3] = (int)(e % r);
+  x[2] = (int)((e / r) % r);
+  x[1] = (int)((e / ((int64_t)r * r)) % r);
+  x[0] = (int)(e / ((int64_t)r * r * r));
+  out[e] += c * A[x[a0] * r + x[a1]] * B[x[b0] * r + x[b1]];
+}
+
+__global__ void k_trace12(int r, const double *__restrict__ in, double *__restrict__ out, int accumulate) {
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= r * r) return;
+  const int k = e / r, s = e % r;
+  const int64_t r2 = (int64_t)r * r, r3 = r2 * r;
+  double v = 0.0;
+  for (int q = 0; q < r; ++q) v += in[k * r3 + q * r2 + q * r + s];
+  out[e] = accumulate ? out[e] + v : v;
+}
+
+struct TraceArgs {
+  const double *in[8];
+};
+
+// One block per array: sum over the r^2 diagonal pairs in a fixed order.
+__global__ void __launch_bounds__(256) k_pair_traces(int r, const TraceArgs a, double *traces) {
+  __shared__ double red[256];
+  const double *in = a.in[blockIdx.x];
+  const int64_t r2 = (int64_t)r * r;
+  double v = 0.0;
+  for (int64_t pq = threadIdx.x; pq < r2; pq += 256) v += in[pq * r2 + pq];
+  red[threadIdx.x] = v;
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if ((int)threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) traces[blockIdx.x] = red[0];
+}
+
+struct UpdateArgs {
+  double *d2[3];
+  const double *U[3];
+};
+
+__global__ void __launch_bounds__(256) k_spin_update(int r, double eps, const UpdateArgs a, const double *traces) {
+  const int64_t n = (int64_t)r * r * r * r;
+  const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  const int q = blockIdx.y;
+  if (e >= n) return;
+  const double t0 = traces[q], tu = traces[3 + q];
+  // a block with zero input trace (fewer than two electrons of its pair kind)
+  // is set to zero
+  const double scale = t0 != 0.0 ? t0 / (t0 + eps * tu) : 0.0;
+  a.d2[q][e] = (a.d2[q][e] + eps * a.U[q][e]) * scale;
+}
+
+__global__ void k_spin_1rdm(int r, double c, const double *__restrict__ aa, const double *__restrict__ bb,
+                            const double *__restrict__ ab, double *__restrict__ ga, double *__restrict__ gb) {
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= r * r) return;
+  const int p = e / r, s = e % r;
+  const int64_t r2 = (int64_t)r * r, r3 = r2 * r;
+  double va = 0.0, vb = 0.0;
+  for (int q = 0; q < r; ++q) {
+    va += aa[p * r3 + q * r2 + s * r + q] + ab[p * r3 + q * r2 + s * r + q];   // 2D(pa q|sa q)
+    vb += bb[p * r3 + q * r2 + s * r + q] + ab[q * r3 + p * r2 + q * r + s];   // 2D(pb q|sb q)
+  }
+  ga[e] = c * va;
+  gb[e] = c * vb;
+}
+
+inline dim3 grid1(int64_t n) { return dim3((unsigned)((n + 255) / 256)); }
+
+}  // namespace
+
+hipError_t launch_combine4(int r, const Terms4 &terms, double *out, int accumulate, const ActiveBits *mask,
+                           hipStream_t s) {
+  const int64_t n = (int64_t)r * r * r * r;
+  hipLaunchKernelGGL(k_combine4, grid1(n), dim3(256), 0, s, r, terms, out, accumulate, mask ? 1 : 0,
+                     mask ? *mask : ActiveBits{});
+  return hipGetLastError();
+}
+
+hipError_t launch_pack_op4(int r, const Terms4 &terms, double *out, int ld, hipStream_t s) {
+  hipLaunchKernelGGL(k_pack_op4, grid1((int64_t)r * r * ld), dim3(256), 0, s, r, terms, out, ld);
+  return hipGetLastError();
+}
+
+hipError_t launch_outer4(int r, double c, const double *A, int a0, int a1, const double *B, int b0, int b1,
+                         double *out, hipStream_t s) {
+  hipLaunchKernelGGL(k_outer4, grid1((int64_t)r * r * r * r), dim3(256), 0, s, r, c, A, a0, a1, B, b0, b1, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_trace12(int r, const double *in, double *out, int accumulate, hipStream_t s) {
+  hipLaunchKernelGGL(k_trace12, grid1((int64_t)r * r), dim3(256), 0, s, r, in, out, accumulate);
+  return hipGetLastError();
+}
+
+hipError_t launch_pair_traces(int r, int count, const double *const *in, double *traces, hipStream_t s) {
+  TraceArgs a{};
+  for (int q = 0; q < count && q < 8; ++q) a.in[q] = in[q];
+  hipLaunchKernelGGL(k_pair_traces, dim3(count), dim3(256), 0, s, r, a, traces);
+  return hipGetLastError();
+}
+
+hipError_t launch_spin_update(int r, double eps, double *const *d2, const double *const *U, const double *traces,
+                              hipStream_t s) {
+  UpdateArgs a{};
+  for (int q = 0; q < 3; ++q) { a.d2[q] = d2[q]; a.U[q] = U[q]; }
+  const int64_t n = (int64_t)r * r * r * r;
+  hipLaunchKernelGGL(k_spin_update, dim3((unsigned)((n + 255) / 256), 3), dim3(256), 0, s, r, eps, a, traces);
+  return hipGetLastError();
+}
+
+hipError_t launch_spin_1rdm(int r, int N, const double *d2aa, const double *d2bb, const double *d2ab, double *ga,
+                            double *gb, hipStream_t s) {
+  hipLaunchKernelGGL(k_spin_1rdm, grid1((int64_t)r * r), dim3(256), 0, s, r, 2.0 / (N - 1), d2aa, d2bb, d2ab, ga,
+                     gb);
+  return hipGetLastError();
+}
+
+}  // namespace acse

@@ -78,7 +78,7 @@ def test_struct_layouts_match_header(tmp_path):
         pytest.skip("gcc not available")
     inc = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "include")
     src = tmp_path / "layout.c"
-    structs = (("acse_problem", acse.Problem), ("acse_options", acse.Options),
+    structs = (("acse_problem", acse.Problem), ("acse_problem_spin", acse.ProblemSpin), ("acse_options", acse.Options),
                ("acse_profile_data", acse.ProfileData), ("acse_solve_options", acse.SolveOptions),
                ("acse_trial", acse.Trial), ("acse_solve_result", acse.SolveResult))
     fields = {st: [f for f, _ in cls._fields_] for st, cls in structs}
