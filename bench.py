@@ -63,6 +63,8 @@ def parse():
     ap.add_argument("--solve-iters", type=int, default=5)
     ap.add_argument("--ny-steps", type=int, default=5,
                     help="steps of the Nakatsuji-Yasuda leg (FP64); 0 skips it")
+    ap.add_argument("--spin-steps", type=int, default=5,
+                    help="steps of the open-shell (N_alpha != N_beta) leg at r = 50 (FP64); 0 skips it")
     ap.add_argument("--solve-eps", type=float, default=1e-5,
                     help="first step size of the acse_solve leg (the synthetic r = 50 integrals are "
                          "large: eps = 1e-3 raises ||R|| at the first trial)")
@@ -80,7 +82,7 @@ TRAITS = {"fp64": "TrF64", "fp32": "TrF32", "bf16x3": "TrBF16x3"}
 
 def gemm_kernel_name(prec, cfg):
     if prec == "int8crt":
-        return "acse::(anonymous namespace)::gemm_crt_kernel"
+        return "acse::(anonymous namespace)::gemm_mod_kernel"
     bm, bn, bk, ns = TILE_SHAPES[prec][cfg]
     wpe = 2 if prec == "fp64" and bm * bn >= 128 * 128 else 1   # register cap of the instantiation
     return f"acse::gemm_nt_kernel<acse::{TRAITS[prec]}, {bm}, {bn}, {bk}, {ns}, {wpe}>"
@@ -285,6 +287,97 @@ def bench_ny(acse, ctx, prob, work, pristine, torch, stream, steps, warmup, eps,
                           "kernel": "gemm_nt_kernel on the NY block products (18 per map, one with its summed pair packed; "
                                     "HIP-event time of their launches)"},
                 energy_identity_rel=abs((E1 - E0) + eps * n2) / (eps * n2))
+
+
+SPIN_GOLDEN = os.path.join(ROOT, "tests", "golden", "r50_spin_step.json")
+
+
+def spin_map_flops(r):
+    """Algorithmic flops of the block products of one spin-block map: 17
+    products of r^2 x r^2 x r^2 (the Y, W H and E terms over spin blocks)."""
+    return 17 * 2.0 * r ** 6
+
+
+def bench_spin(acse, ctx, gen, torch, steps, warmup, eps, name="r50s"):
+    """One acse_step_spin per step on the open-shell workload (r = 50,
+    N_alpha = 16, N_beta = 14): the residual, the update map, the per-block
+    Euler step with trace restoration, the 1-RDMs per spin and the energy, in
+    FP64.  Inputs restored from a pristine device copy inside the timed region.
+    Checked against the stored FP64 oracle values of the same step."""
+    dev = torch.device("cuda", 0)
+    p = gen.named_spin(name)
+    r = p["r"]
+    h = torch.as_tensor(p["h"], device=dev).contiguous()
+    V = torch.as_tensor(p["V"], device=dev).contiguous()
+    keys = ("gamma_a", "gamma_b", "d2aa", "d2bb", "d2ab")
+    pristine = [torch.as_tensor(p[k], device=dev).contiguous() for k in keys]
+    work = [t.clone() for t in pristine]
+    prob = acse.ProblemSpin(r, p["Na"], p["Nb"], h.data_ptr(), V.data_ptr(), *[t.data_ptr() for t in work])
+    outs = [torch.empty((r, r, r, r), dtype=torch.float64, device=dev) for _ in range(6)]
+    opts = acse.Context.options("fp64")
+    stream = ctx.stream
+
+    def restore():
+        for w, q in zip(work, pristine):
+            w.copy_(q)
+
+    for _ in range(warmup):
+        restore()
+        ctx.step_spin_raw(prob, eps, opts, outs, want=False)
+    torch.cuda.synchronize()
+    ctx.profile(True)
+    start = torch.cuda.Event(enable_timing=True)
+    stop = torch.cuda.Event(enable_timing=True)
+    start.record(stream)
+    for _ in range(steps):
+        restore()
+        ctx.step_spin_raw(prob, eps, opts, outs, want=False)
+    stop.record(stream)
+    torch.cuda.synchronize()
+    ms = start.elapsed_time(stop) / steps
+    prof = ctx.profile_read()
+    ctx.profile(False)
+    # residual-only rate
+    R = outs[:3]
+    ctx.residual_spin_raw(prob, opts, *R, want_norm=False)
+    torch.cuda.synchronize()
+    s2 = torch.cuda.Event(enable_timing=True)
+    e2 = torch.cuda.Event(enable_timing=True)
+    s2.record(stream)
+    for _ in range(steps):
+        ctx.residual_spin_raw(prob, opts, *R, want_norm=False)
+    e2.record(stream)
+    torch.cuda.synchronize()
+    res_ms = s2.elapsed_time(e2) / steps
+    restore()
+    E1, n2 = ctx.step_spin_raw(prob, eps, opts, outs)
+    err = None
+    if os.path.exists(SPIN_GOLDEN):
+        g = json.load(open(SPIN_GOLDEN))
+        idx = [tuple(t) for t in g["index"]]
+        got = dict(zip(("R_aa", "R_bb", "R_ab", "U_aa", "U_bb", "U_ab"), [o.cpu().numpy() for o in outs]))
+        got.update(zip(("d2aa", "d2bb", "d2ab"), [w.cpu().numpy() for w in work[2:]]))
+        err = dict(dE=abs(E1 - g["energy1"]), norm2_rel=abs(n2 - g["norm2"]) / g["norm2"])
+        for k, v in got.items():
+            ref = np.array(g["samples"][k])
+            val = np.array([v[t] for t in idx])
+            err[f"{k}_sample_rel"] = float(np.abs(val - ref).max() / max(np.abs(ref).max(), 1e-300))
+            err[f"{k}_norm_rel"] = abs(float(np.linalg.norm(v)) - g["norms"][k]) / max(g["norms"][k], 1e-300)
+    restore()
+    gemm_ms, gemm_n = prof["gemm"]
+    flops = 2 * spin_map_flops(r)          # two maps per step
+    achieved = flops / (gemm_ms / steps * 1e-3) / 1e12
+    return dict(
+        workload=f"{name}: r={r}, N_alpha={p['Na']}, N_beta={p['Nb']}, three 2-RDM spin blocks, one "
+                 f"acse_step_spin (eps={eps}) per step, FP64",
+        ms_per_step=ms, steps_per_s=1e3 / ms, residual_ms=res_ms, residual_evals_per_s=1e3 / res_ms,
+        stage_ms_per_step={k: v[0] / steps for k, v in prof.items()},
+        block_gemm_flops_per_step=flops, useful_tflops_step=flops / (ms * 1e-3) / 1e12,
+        roofline={"bound": "mfma", "achieved": achieved, "peak": PEAK_TFLOPS["fp64"], "unit": "TFLOP/s",
+                  "frac": achieved / PEAK_TFLOPS["fp64"],
+                  "kernel": "gemm_nt_kernel<TrF64> on the 17 spin-block products per map (HIP-event time of "
+                            "their launches)"},
+        error_vs_oracle=err, energy1=E1, norm2=n2)
 
 
 def cpu_model():
@@ -508,6 +601,8 @@ def main():
             mode: bench_ny(acse, ctx, prob, work, pristine, torch, stream, args.ny_steps, min(args.warmup, 2),
                            args.eps, results[mode]["ms_per_step"], mode)
             for mode in args.modes.split(",")}
+    if args.spin_steps > 0:
+        line["non_singlet"] = bench_spin(acse, ctx, gen, torch, args.spin_steps, min(args.warmup, 2), args.eps)
     if args.vjp_modes:
         line["vjp"] = bench_vjp(acse, gen, torch, args.vjp_modes.split(","), max(3, args.steps // 2),
                                 args.warmup)

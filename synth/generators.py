@@ -37,6 +37,10 @@ CONFIGS = {
     "r50": dict(r=50, N=30, n_chol=60),
     "vjp30": dict(r=30, N=20, n_chol=60),
 }
+# Named workloads of states of any S_z: (r, N_alpha, N_beta, n_chol).
+SPIN_CONFIGS = {
+    "r50s": dict(r=50, Na=16, Nb=14, n_chol=60),
+}
 BATCH_SIZES = (20, 28, 36, 44)
 
 
@@ -115,6 +119,11 @@ def problem(r, N, n_chol, seed=0, pinned=()):
 def named(name, seed=0):
     c = CONFIGS[name]
     return problem(c["r"], c["N"], c["n_chol"], seed)
+
+
+def named_spin(name, seed=0):
+    c = SPIN_CONFIGS[name]
+    return spin_problem(c["r"], c["Na"], c["Nb"], c["n_chol"], seed)
 
 
 def batched_problems(seed=0, sizes=BATCH_SIZES):

@@ -6,6 +6,9 @@ relative 1e-10.  Sizes span several GEMM tiles with ragged tails (r^2 = 16 ...
 576 against 64/128 tiles); electron counts cover doublets, triplets,
 S_z = 3/2 and an empty beta shell.
 """
+import json
+import os
+
 import numpy as np
 import pytest
 
@@ -170,3 +173,35 @@ def test_spin_step_identities_and_errors(acse, ctx):
     singlet, _ = ctx.problem(p["h"], p["V"], p["gamma_a"], p["d2aa"], p["d2ab"], p["Na"], n_beta=p["Nb"])
     with pytest.raises(acse.AcseError, match="_spin calls"):
         ctx.residual_raw(singlet, ctx.options(), R[0], R[1])
+
+
+SPIN_GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "r50_spin_step.json")
+
+
+def test_r50_spin_step_vs_stored_oracle(acse):
+    """Full size (r = 50, N_alpha = 16, N_beta = 14), the configuration the
+    bench times: sampled elements of the R, U and new 2-RDM blocks, the block
+    norms, ||R||^2, E before and after the step and both new 1-RDMs against the
+    stored oracle values (tests/golden/make_golden_spin.py), FP64 at 1e-10."""
+    g = json.load(open(SPIN_GOLDEN))
+    p = gen.named_spin(g["workload"])
+    assert (p["r"], p["Na"], p["Nb"]) == (g["r"], g["Na"], g["Nb"]) == (50, 16, 14)
+    print("[spin fullsize] r50s step", flush=True)
+    ctx = acse.Context(r_max=50)
+    try:
+        e0 = ctx.energy_spin(p["h"], p["V"], p["d2aa"], p["d2bb"], p["d2ab"], p["Na"], p["Nb"])
+        out = ctx.step_spin(*_args(p), eps=g["eps"], return_ru=True)
+        idx = tuple(np.array(g["index"]).T)
+        for k in g["samples"]:
+            got = cpu(out[k])
+            ref = np.array(g["samples"][k])
+            assert np.abs(got[idx] - ref).max() <= TOL * np.abs(ref).max(), k
+            assert abs(np.linalg.norm(got) - g["norms"][k]) <= TOL * g["norms"][k], k
+        assert abs(out["norm2"] - g["norm2"]) <= TOL * g["norm2"]
+        assert abs(e0 - g["energy0"]) <= TOL * abs(g["energy0"])
+        assert abs(out["energy"] - g["energy1"]) <= 1e-13 * abs(g["energy1"])
+        assert abs(out["energy"] - g["energy1"]) < 1e-7
+        for k, ok in (("d1a", "gamma_a"), ("d1b", "gamma_b")):
+            assert np.abs(cpu(out[k]) - np.array(g[ok])).max() <= TOL, k
+    finally:
+        ctx.close()
