@@ -325,11 +325,16 @@ acse_status acse_energy_vjp(acse_ctx ctx, const acse_problem *prob, double Ebar,
                             double *V_bar, double *d2aa_bar, double *d2ab_bar);
 
 /* Stage timing with HIP events recorded on the context's stream.  Stages:
- *   0  RDM-side operands (W = Gamma2 - 2/3 Gamma1^Gamma1 and its layouts)
+ *   0  RDM-side operands (W = Gamma2 - 2/3 Gamma1^Gamma1 and its layouts;
+ *      with ACSE_INT8CRT also their residues)
  *   1  fold of the reduced Hamiltonian (Eq. (2))
- *   2  O(r^4)/O(r^5) transforms feeding the contractions
- *   3  grouped pair-index GEMM (the six O(r^6) contractions of one map)
- *   4  assembly, (ij)<->(kl) exchange and the FP64 norm
+ *   2  O(r^4)/O(r^5) transforms feeding the contractions (with
+ *      ACSE_INT8CRT also the X-side residues)
+ *   3  grouped pair-index GEMM (the six O(r^6) contractions of one map; with
+ *      ACSE_INT8CRT the modular int8 products alone; on the spin-block path
+ *      its 17 block products)
+ *   4  assembly, (ij)<->(kl) exchange and the FP64 norm (with ACSE_INT8CRT
+ *      also the reconstruction of the products from their residues)
  *   5  step tail: axpy, trace restoration, 1-RDM contraction, energy
  *   6  Nakatsuji-Yasuda share, whole (cumulant blocks, operand builds, its
  *      block GEMMs, unscrambling and the combination into the map;

@@ -839,6 +839,10 @@ acse_status run_map(acse_ctx c, const acse_problem *p, GemmPrec prec, int cfg, c
       StageTimer t3(c, 3);
       HIP_TRY(c, gemm_crt_launch(batch, c->crt, c->stream));
     }
+    {
+      StageTimer t4(c, 4);  // the reconstruction writes the products' 4-index outputs
+      HIP_TRY(c, crt_combine_launch(batch, c->crt, c->stream));
+    }
     return map_back(c, p, sigma, Oaa, Oab, act, Maa, Mab, w.scal + slot, w, Xaa, Xab, prec, cfg);
   }
   map_probs(w, prec, r, batch.p);

@@ -44,17 +44,26 @@ struct ResidueBatch {
 };
 hipError_t launch_to_residues(const ResidueBatch &b, const CrtTable &T, hipStream_t s);
 
-// Per-XCD ranges of the per-modulus tile order of the modular product.
+// Work of the modular product by XCD: entry e is every tile of problem
+// prob[e] for modulus mod[e]; XCD c runs entries xs[c] .. xs[c+1]-1 in that
+// order, entry e from its local tile start[e] on.
+constexpr int kMaxModPairs = 6 * kMaxModuli;
 struct ModSched {
   int xs[kGemmXcds + 1];
+  int start[kMaxModPairs];
+  uint8_t prob[kMaxModPairs], mod[kMaxModPairs];
 };
 
-// Grouped modular product and reconstruction: for each problem, A and B point
-// at plane 0 of the residue operands (planes plane_a / plane_b bytes apart,
-// rows of ld bytes, Kp = ld a multiple of kCrtKPad), ea / eb the row
-// exponents, kshift = 2k, and Y at crt_residue_out_bytes(M, N) bytes per
-// modulus for the residues of the product.  Writes C through the store map.
+// Grouped modular product: for each problem, A and B point at plane 0 of the
+// residue operands (planes plane_a / plane_b bytes apart, rows of ld bytes,
+// Kp = ld a multiple of kCrtKPad), and Y at crt_residue_out_bytes(M, N) bytes
+// per modulus receives the residues of the product.  Fills in the batch's
+// tile bookkeeping.
 hipError_t gemm_crt_launch(GemmBatch &b, const CrtTable &T, hipStream_t s);
+// Reconstruction of the batch launched by gemm_crt_launch (same stream, after
+// it): from the residues in Y, ea / eb the row exponents and kshift = 2k,
+// writes C through the store map.
+hipError_t crt_combine_launch(const GemmBatch &b, const CrtTable &T, hipStream_t s);
 int64_t crt_residue_out_bytes(int M, int N);
 
 }  // namespace acse

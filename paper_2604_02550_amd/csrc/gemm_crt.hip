@@ -27,6 +27,7 @@
 // the reconstruction (one thread per four rows of one column).
 #include <algorithm>
 #include <cmath>
+#include <vector>
 
 #include "gemm_crt.h"
 
@@ -198,26 +199,24 @@ __device__ __forceinline__ void mod_tile(const GemmProb &P, const CrtTable &T, i
     }
 }
 
-// Work of the modular product: every (modulus, product, tile).  Each XCD
-// (own L2) works through its share of every product (the c-th eighth of each,
-// as seg_* lists them) modulus by modulus, so all XCDs are on the same modulus
-// at about the same time and its operand planes (about 1/13 of the total)
-// stay cached.  sched.xs[c] .. xs[c+1]: XCD c's range of the per-modulus
-// logical tile list.
+// Work of the modular product: every (product, modulus) pair runs whole on
+// one XCD (own L2), so the tiles that XCD's CUs hold at one time are a compact
+// block of one product and share their operand panels in its L2.  Workgroups
+// go to XCDs round-robin by index (blockIdx.x % 8), and each XCD starts its
+// workgroups in index order.
 __global__ void __launch_bounds__(kNT) __attribute__((amdgpu_waves_per_eu(2)))
 gemm_mod_kernel(const GemmBatch batch, const CrtTable tab, const ModSched sched) {
   const int c = blockIdx.x % kGemmXcds, s = blockIdx.x / kGemmXcds;
-  const int share = sched.xs[c + 1] - sched.xs[c];
-  if (share == 0) return;
-  const int j = s / share;
-  if (j >= tab.nmod) return;
-  const int t = sched.xs[c] + (s - j * share);
-  int lo = 0, hi = batch.nseg - 1;
+  int lo = sched.xs[c], hi = sched.xs[c + 1] - 1;
+  if (hi < lo || s < sched.start[lo]) return;
   while (lo < hi) {
     const int mid = (lo + hi + 1) >> 1;
-    if (batch.seg_start[mid] <= t) lo = mid; else hi = mid - 1;
+    if (sched.start[mid] <= s) lo = mid; else hi = mid - 1;
   }
-  mod_tile(batch.p[batch.seg_prob[lo]], tab, j, batch.seg_local[lo] + t - batch.seg_start[lo]);
+  const GemmProb &P = batch.p[sched.prob[lo]];
+  const int local = s - sched.start[lo];
+  if (local >= P.tiles_m * P.tiles_n) return;
+  mod_tile(P, tab, sched.mod[lo], local);
 }
 
 // Reconstruction: one thread per (product, row quad, column).
@@ -447,30 +446,53 @@ hipError_t gemm_crt_launch(GemmBatch &b, const CrtTable &T, hipStream_t s) {
   }
   b.total_tiles = total;
   if (total == 0) return hipSuccess;
-  // per-modulus logical order: the c-th eighth of every product, c = 0 .. 7
-  ModSched sched{};
-  b.nseg = 0;
-  int start = 0;
-  for (int c = 0; c < kGemmXcds; ++c) {
-    sched.xs[c] = start;
+  // Longest-first assignment of the (product, modulus) pairs to XCDs by cost
+  // (tiles x K slabs), then each XCD's pairs in modulus order, so that the XCDs
+  // work on few moduli at a time and the Infinity Cache holds their planes.
+  if (b.count * T.nmod > kMaxModPairs) return hipErrorInvalidValue;
+  struct Pair { int q, j; int64_t cost; };
+  std::vector<Pair> pairs;
+  for (int j = 0; j < T.nmod; ++j)
     for (int q = 0; q < b.count; ++q) {
-      const int n = b.p[q].tiles_m * b.p[q].tiles_n;
-      const int lo = (int)((int64_t)n * c / kGemmXcds), hi = (int)((int64_t)n * (c + 1) / kGemmXcds);
-      if (hi <= lo) continue;
-      b.seg_start[b.nseg] = start;
-      b.seg_prob[b.nseg] = q;
-      b.seg_local[b.nseg] = lo;
-      ++b.nseg;
-      start += hi - lo;
+      const GemmProb &p = b.p[q];
+      const int64_t tiles = (int64_t)p.tiles_m * p.tiles_n;
+      if (tiles > 0) pairs.push_back({q, j, tiles * (p.Kp / kBK)});
     }
+  std::vector<int> order(pairs.size());
+  for (size_t e = 0; e < order.size(); ++e) order[e] = (int)e;
+  std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return pairs[x].cost > pairs[y].cost; });
+  int64_t load[kGemmXcds] = {};
+  std::vector<int> owner(pairs.size());
+  for (int e : order) {
+    int best = 0;
+    for (int c = 1; c < kGemmXcds; ++c)
+      if (load[c] < load[best]) best = c;
+    owner[e] = best;
+    load[best] += pairs[e].cost;
   }
-  sched.xs[kGemmXcds] = start;
-  b.seg_start[b.nseg] = start;
-  int share = 0;
-  for (int c = 0; c < kGemmXcds; ++c) share = std::max(share, sched.xs[c + 1] - sched.xs[c]);
-  hipLaunchKernelGGL(gemm_mod_kernel, dim3(kGemmXcds * share * T.nmod), dim3(kNT), 0, s, b, T, sched);
-  hipError_t e = hipGetLastError();
-  if (e != hipSuccess) return e;
+  ModSched sched{};
+  int n = 0, share = 0;
+  for (int c = 0; c < kGemmXcds; ++c) {
+    sched.xs[c] = n;
+    int t = 0;
+    for (size_t e = 0; e < pairs.size(); ++e) {  // pairs are listed modulus-major
+      if (owner[e] != c) continue;
+      sched.start[n] = t;
+      sched.prob[n] = (uint8_t)pairs[e].q;
+      sched.mod[n] = (uint8_t)pairs[e].j;
+      t += b.p[pairs[e].q].tiles_m * b.p[pairs[e].q].tiles_n;
+      ++n;
+    }
+    share = std::max(share, t);
+  }
+  sched.xs[kGemmXcds] = n;
+  b.nseg = 0;
+  hipLaunchKernelGGL(gemm_mod_kernel, dim3(kGemmXcds * share), dim3(kNT), 0, s, b, T, sched);
+  return hipGetLastError();
+}
+
+hipError_t crt_combine_launch(const GemmBatch &b, const CrtTable &T, hipStream_t s) {
+  if (b.total_tiles == 0) return hipSuccess;
   int64_t most = 0;
   for (int q = 0; q < b.count; ++q) most = std::max(most, (int64_t)((b.p[q].M + 3) / 4) * b.p[q].N);
   hipLaunchKernelGGL(k_crt_combine, dim3((unsigned)((most + 255) / 256), b.count), dim3(256), 0, s, b, T);
