@@ -92,8 +92,10 @@ def gemm_kernel_name(prec, cfg):
 
 def bench_batched(acse, ctx, gen, torch, modes, steps, warmup):
     """Twelve instances (r in {20, 28, 36, 44}, ground + 2 excited states each):
-    one acse_residual_batched call per step against twelve acse_residual calls
-    (each with its own autotuned tile configuration)."""
+    one acse_residual_batched call per step (default: each instance on its own
+    side-stream lane; and with ACSE_FLAG_BATCH_PERSISTENT: all products in one
+    persistent launch) against twelve acse_residual calls in order on one
+    stream (each with its own autotuned tile configuration)."""
     dev = torch.device("cuda", 0)
     batch = gen.batched_problems(seed=0)
     probs, keep, outs = [], [], []
@@ -108,9 +110,9 @@ def bench_batched(acse, ctx, gen, torch, modes, steps, warmup):
     res = {}
     for mode in modes:
         opts = acse.Context.options(mode)
-        best, tile_ms = ctx.autotune_batched_raw(probs, opts)
-        for prob in probs:
-            ctx.autotune_raw(prob, opts)
+        popts = acse.Context.options(mode, flags=acse.FLAG_BATCH_PERSISTENT)
+        ctx.autotune_batched_raw(probs, opts)          # every r, as single calls take them
+        best, tile_ms = ctx.autotune_batched_raw(probs, popts)
 
         def timed(fn):
             for _ in range(warmup):
@@ -128,22 +130,27 @@ def bench_batched(acse, ctx, gen, torch, modes, steps, warmup):
         def batched():
             ctx.residual_batched_raw(probs, opts, Ra, Rb, want_norm=False)
 
+        def persistent():
+            ctx.residual_batched_raw(probs, popts, Ra, Rb, want_norm=False)
+
         def sequential():
             for prob, o in zip(probs, outs):
                 ctx.residual_raw(prob, opts, o[0], o[1], want_norm=False)
 
         ms_b = timed(batched)
+        ms_p = timed(persistent)
         ms_s = timed(sequential)
         ctx.profile(True)
-        batched()
+        persistent()
         prof = ctx.profile_read()
         ctx.profile(False)
         gemm_ms = prof["gemm"][0]
         res[mode] = dict(instances=len(batch), sizes=sorted({p["r"] for p in batch}),
-                         batched_ms=ms_b, sequential_ms=ms_s,
+                         batched_ms=ms_b, persistent_ms=ms_p, sequential_ms=ms_s,
                          batched_evals_per_s=len(batch) * 1e3 / ms_b,
                          sequential_evals_per_s=len(batch) * 1e3 / ms_s,
-                         speedup=ms_s / ms_b, tile_config=best, tile_gemm_ms=tile_ms,
+                         speedup=ms_s / ms_b, persistent_speedup=ms_s / ms_p,
+                         persistent_tile_config=best, persistent_tile_gemm_ms=tile_ms,
                          persistent_gemm_ms=gemm_ms,
                          persistent_gemm_tflops=flops / (gemm_ms * 1e-3) / 1e12,
                          useful_tflops=flops / (ms_b * 1e-3) / 1e12)

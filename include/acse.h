@@ -178,6 +178,12 @@ typedef enum { ACSE_RECON_V = 0, ACSE_RECON_NY = 1 } acse_reconstruction;
  * inputs give results that are no residual of any state. */
 #define ACSE_FLAG_CHECK_INPUTS 2
 
+/* acse_options.flags, acse_residual_batched and acse_autotune_batched only
+ * (ignored by the other calls): run the pair-index products of all instances
+ * as one persistent launch between the per-instance stages instead of each
+ * instance's own grouped launch on its side stream. */
+#define ACSE_FLAG_BATCH_PERSISTENT 4
+
 /* Creates a context on HIP device `device`, ordering work on `hip_stream`
  * (a hipStream_t; NULL = the default stream), with workspace for problems up
  * to r_max spatial orbitals.  Returns ACSE_ERR_NOMEM if the workspace does
@@ -364,18 +370,25 @@ acse_status acse_autotune(acse_ctx ctx, const acse_problem *prob, const acse_opt
 
 /* Batched residual of Eq. (4) over `count` independent instances (1 <= count
  * <= 4096) of possibly different r, each r <= r_max: ground and excited
- * states, several molecules.  Per instance, the RDM operands, the fold and
- * the transforms run as in acse_residual.  The six pair-index products of
- * all instances then run in one persistent launch: a grid sized to the
- * resident capacity walks one tile list ordered by decreasing K.  The
- * per-instance assembly follows.
+ * states, several molecules.  Each instance runs the launches of its own
+ * acse_residual call (RDM operands, fold, transforms, its grouped product
+ * launch, assembly) in order on one of four side streams (largest instances
+ * first, each to the least loaded stream), so one instance's memory-bound
+ * stages overlap another's products; the context's stream waits for all of
+ * them.  With ACSE_FLAG_BATCH_PERSISTENT (and always with the
+ * Nakatsuji-Yasuda reconstruction) the per-instance stages before and after
+ * the products run on the side streams and the six pair-index products of
+ * all instances run in between as one persistent launch: a grid sized to the
+ * resident capacity walks one tile list ordered by decreasing K.
  *   probs       host array [count]
  *   R_aa, R_ab  host arrays [count] of device pointers, [r_i^4] each
  *   norm2_host  host [count] (||R_i||^2 as in acse_residual) or NULL;
  *               if not NULL the call synchronises
- *   opts        apply to every instance.  tile = -1 takes the configuration
- *               acse_autotune_batched chose for this (precision, list of r),
- *               else the size default.
+ *   opts        apply to every instance.  tile = -1: per instance the
+ *               configuration a single call of that r takes (acse_autotune's
+ *               choice for (r, precision), else the size default); with
+ *               ACSE_FLAG_BATCH_PERSISTENT the one acse_autotune_batched
+ *               chose for this (precision, list of r), else the size default.
  * The first call (and any call that needs more room) allocates a batch
  * workspace kept until acse_destroy.  Errors are as for acse_residual; the
  * detail names the failing instance. */
@@ -383,7 +396,10 @@ acse_status acse_residual_batched(acse_ctx ctx, int32_t count, const acse_proble
                                   const acse_options *opts, double *const *R_aa,
                                   double *const *R_ab, double *norm2_host);
 
-/* Autotuner of the batched launch: times the persistent product launch of this
+/* Autotuner of the batched call.  Default: runs acse_autotune on one instance
+ * of each distinct r (each choice cached for (r, precision), as the batched
+ * call takes them) and reports the outputs of the largest r.  With
+ * ACSE_FLAG_BATCH_PERSISTENT: times the persistent product launch of this
  * batch under every tile configuration and caches the fastest for
  * (precision, list of r).  Outputs as for acse_autotune.  Synchronises. */
 acse_status acse_autotune_batched(acse_ctx ctx, int32_t count, const acse_problem *probs,

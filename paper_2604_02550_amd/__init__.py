@@ -68,6 +68,7 @@ RECON_V, RECON_NY = 0, 1
 
 FLAG_GENERAL_KERNELS = 1
 FLAG_CHECK_INPUTS = 2
+FLAG_BATCH_PERSISTENT = 4
 
 EULER_FIXED, EULER_BACKTRACK, EULER_QUADRATIC = 0, 1, 2
 CONTROLS = {"fixed": EULER_FIXED, "backtrack": EULER_BACKTRACK, "quadratic": EULER_QUADRATIC}

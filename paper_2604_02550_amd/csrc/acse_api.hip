@@ -269,7 +269,7 @@ acse_status validate(acse_ctx c, const acse_problem *p, const acse_options *o, b
                                            "reconstruction only");
     if (o->tile < -1 || o->tile >= gemm_num_tiles(GEMM_F64))
       return fail(c, ACSE_ERR_ARG, "tile configuration out of range");
-    if (o->flags & ~(ACSE_FLAG_GENERAL_KERNELS | ACSE_FLAG_CHECK_INPUTS))
+    if (o->flags & ~(ACSE_FLAG_GENERAL_KERNELS | ACSE_FLAG_CHECK_INPUTS | ACSE_FLAG_BATCH_PERSISTENT))
       return fail(c, ACSE_ERR_ARG, "unknown option flags");
     if (o->reconstruction != ACSE_RECON_V && o->reconstruction != ACSE_RECON_NY)
       return fail(c, ACSE_ERR_ARG, "unknown reconstruction");
@@ -2143,11 +2143,60 @@ acse_status join_sides(acse_ctx c, int ns) {
   return ACSE_OK;
 }
 
+// Tile configuration of one instance's products: the caller's, else the one
+// tuned for (r, precision), else the size default (as a single call takes it).
+int instance_cfg(acse_ctx c, GemmPrec prec, int r, int tile) {
+  if (tile >= 0) return tile;
+  auto it = c->tuned.find({r, (int)prec});
+  return it != c->tuned.end() ? it->second : gemm_default_cfg(prec, r * r, r * r);
+}
+
+// Lanes: every instance runs its whole residual (RDM operands, fold,
+// transforms, its own grouped product launch, assembly) in order on one side
+// stream, so the memory-bound stages of one instance overlap the products of
+// another.  Each instance's launches are those of a single acse_residual call
+// with the same tile configuration.
+acse_status run_lanes(acse_ctx c, int count, const acse_problem *probs, GemmPrec prec, int tile,
+                      double *const *Raa, double *const *Rab, BatchPlan &plan, const std::vector<int> &order,
+                      const std::vector<int> &lane, int ns) {
+  acse_status st;
+  if ((st = fork_sides(c, ns)) != ACSE_OK) return st;
+  const ActiveBits none{};
+  auto one = [&](int i) -> acse_status {
+    const acse_problem *p = &probs[i];
+    Workspace &w = plan.ws[i];
+    StreamSwap sw(c, c->side[lane[i]]);
+    acse_status s2 = prep_rdm_operands(c, p, prec, w);
+    if (s2 != ACSE_OK) return s2;
+    {
+      StageTimer t1(c, 1);
+      HIP_TRY(c, launch_fold(p->r, p->n_alpha + p->n_beta, p->h, p->V, w.Aaa, w.Aab, c->stream));
+    }
+    if ((s2 = map_front(c, p, prec, w.Aaa, w.Aab, w)) != ACSE_OK) return s2;
+    GemmBatch b{};
+    b.count = kProbsPerMap;
+    map_probs(w, prec, p->r, b.p);
+    {
+      StageTimer t3(c, 3);
+      HIP_TRY(c, gemm_launch(prec, instance_cfg(c, prec, p->r, tile), b, c->stream));
+    }
+    return map_back(c, p, -1.0, Raa ? Raa[i] : w.Raa, Rab ? Rab[i] : w.Rab, none, nullptr, nullptr,
+                    plan.norms + i, w);
+  };
+  for (int i : order)
+    if ((st = one(i)) != ACSE_OK) break;
+  // a failing launch still rejoins the side streams before returning
+  const acse_status sj = join_sides(c, ns);
+  return st != ACSE_OK ? st : sj;
+}
+
 // Per-instance stages run concurrently on the side streams (largest instances
-// first, each to the least loaded stream); the products of all instances run
-// as one persistent launch on the context stream in between.
+// first, each to the least loaded stream).  Default: lanes (above).  With
+// `persistent` (and always with the NY 3-RDM) the products of all instances
+// run as one persistent launch on the context stream between the fronts and
+// the back ends.
 acse_status run_batched(acse_ctx c, int count, const acse_problem *probs, GemmPrec prec, int cfg,
-                        double *const *Raa, double *const *Rab, BatchPlan &plan) {
+                        double *const *Raa, double *const *Rab, BatchPlan &plan, bool persistent, int tile) {
   acse_status st;
   const int ns = std::min(count, kBatchStreams);
   std::vector<int> order(count), lane(count);
@@ -2163,6 +2212,7 @@ acse_status run_batched(acse_ctx c, int count, const acse_problem *probs, GemmPr
     const double rr = probs[i].r;
     load[best] += rr * rr * rr * rr * rr;
   }
+  if (!persistent && !c->ny_on) return run_lanes(c, count, probs, prec, tile, Raa, Rab, plan, order, lane, ns);
   std::vector<GemmProb> gp(kProbsPerMap * (size_t)count);
   if ((st = fork_sides(c, ns)) != ACSE_OK) return st;
   // a failing launch still rejoins the side streams before returning
@@ -2236,8 +2286,10 @@ extern "C" acse_status acse_residual_batched(acse_ctx ctx, int32_t count, const 
   const GemmPrec prec = prec_of(opts);
   BatchPlan plan;
   if ((st = ensure_batch(ctx, count, probs, plan)) != ACSE_OK) return st;
-  const int cfg = batch_cfg(ctx, prec, count, probs, opts ? opts->tile : -1);
-  if ((st = run_batched(ctx, count, probs, prec, cfg, R_aa, R_ab, plan)) != ACSE_OK) return st;
+  const int tile = opts ? opts->tile : -1;
+  const bool persistent = opts && (opts->flags & ACSE_FLAG_BATCH_PERSISTENT);
+  const int cfg = batch_cfg(ctx, prec, count, probs, tile);
+  if ((st = run_batched(ctx, count, probs, prec, cfg, R_aa, R_ab, plan, persistent, tile)) != ACSE_OK) return st;
   if (norm2_host) {
     HIP_TRY(ctx, hipMemcpyAsync(norm2_host, plan.norms, count * sizeof(double), hipMemcpyDeviceToHost,
                                 ctx->stream));
@@ -2257,6 +2309,28 @@ extern "C" acse_status acse_autotune_batched(acse_ctx ctx, int32_t count, const 
   ctx->ny_on = false;  // the tile choice concerns the Valdemoro products
   if (!best_tile) return fail(ctx, ACSE_ERR_ARG, "best_tile is NULL");
   HIP_TRY(ctx, hipSetDevice(ctx->device));
+  if (!(opts && (opts->flags & ACSE_FLAG_BATCH_PERSISTENT))) {
+    // lanes: each instance's products are a single call's, so tune each r as
+    // acse_autotune does (cached per (r, precision)); report the largest r
+    int big = 0;
+    for (int i = 1; i < count; ++i)
+      if (probs[i].r > probs[big].r) big = i;
+    std::vector<int> seen;
+    for (int i = 0; i < count; ++i) {
+      if (std::find(seen.begin(), seen.end(), probs[i].r) != seen.end()) continue;
+      seen.push_back(probs[i].r);
+      int32_t b = -1;
+      double t[ACSE_NUM_TILE_CONFIGS] = {};
+      if ((st = acse_autotune(ctx, &probs[i], opts, &b, t)) != ACSE_OK)
+        return fail(ctx, st, "instance " + std::to_string(i) + ": " + ctx->err);
+      if (probs[i].r == probs[big].r) {
+        *best_tile = b;
+        if (times_ms)
+          for (int q = 0; q < ACSE_NUM_TILE_CONFIGS; ++q) times_ms[q] = t[q];
+      }
+    }
+    return ACSE_OK;
+  }
   const GemmPrec prec = prec_of(opts);
   BatchPlan plan;
   if ((st = ensure_batch(ctx, count, probs, plan)) != ACSE_OK) return st;
@@ -2268,10 +2342,10 @@ extern "C" acse_status acse_autotune_batched(acse_ctx ctx, int32_t count, const 
   double tms[ACSE_NUM_TILE_CONFIGS] = {};
   for (int cfg = 0; cfg < ACSE_NUM_TILE_CONFIGS; ++cfg) {
     ctx->profiling = false;
-    if ((st = run_batched(ctx, count, probs, prec, cfg, nullptr, nullptr, plan)) != ACSE_OK) break;
+    if ((st = run_batched(ctx, count, probs, prec, cfg, nullptr, nullptr, plan, true, cfg)) != ACSE_OK) break;
     ctx->profiling = true;
     for (int rep = 0; rep < kTuneReps && st == ACSE_OK; ++rep)
-      st = run_batched(ctx, count, probs, prec, cfg, nullptr, nullptr, plan);
+      st = run_batched(ctx, count, probs, prec, cfg, nullptr, nullptr, plan, true, cfg);
     if (st != ACSE_OK) break;
     if (hipStreamSynchronize(ctx->stream) != hipSuccess) { st = fail(ctx, ACSE_ERR_HIP, "sync"); break; }
     double ms = 1e300;  // fastest of the timed repetitions (robust to interference)
@@ -2397,7 +2471,8 @@ acse_status validate_spin(acse_ctx c, const acse_problem_spin *p, const acse_opt
     if (o->reconstruction != ACSE_RECON_V)
       return fail(c, ACSE_ERR_UNSUPPORTED, "the spin-block path takes the Valdemoro reconstruction only");
     if (o->flags & ~ACSE_FLAG_GENERAL_KERNELS)
-      return fail(c, (o->flags & ~(ACSE_FLAG_GENERAL_KERNELS | ACSE_FLAG_CHECK_INPUTS)) ? ACSE_ERR_ARG
+      return fail(c, (o->flags & ~(ACSE_FLAG_GENERAL_KERNELS | ACSE_FLAG_CHECK_INPUTS |
+                                   ACSE_FLAG_BATCH_PERSISTENT)) ? ACSE_ERR_ARG
                                                                                          : ACSE_ERR_UNSUPPORTED,
                   "the spin-block path accepts ACSE_FLAG_GENERAL_KERNELS only");
     if (o->tile < -1 || o->tile >= gemm_num_tiles(GEMM_F64)) return fail(c, ACSE_ERR_ARG, "tile configuration out of range");

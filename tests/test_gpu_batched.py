@@ -1,5 +1,6 @@
 """GPU tests of the batched residual (acse_residual_batched): instances of
-uneven r in one persistent product launch.
+uneven r, each on its own side-stream lane (default) or with all products in
+one persistent launch (ACSE_FLAG_BATCH_PERSISTENT).  Both strategies:
 
 * A small mixed batch (r = 5, 6, 9, 13; ground and pinned excited states)
   against the FP64 oracle, 1e-10.
@@ -64,11 +65,15 @@ def check_oracle(p, Raa, Rab, n2, tol):
     assert abs(n2 - rn2) <= tol * rn2
 
 
+STRATEGIES = {"lanes": 0, "persistent": 4}
+
+
+@pytest.mark.parametrize("strategy", list(STRATEGIES))
 @pytest.mark.parametrize("tile", [-1, 0, 1, 2])
-def test_small_batch_vs_oracle(ctx, tile):
+def test_small_batch_vs_oracle(ctx, tile, strategy):
     batch = small_batch()
-    print(f"[batched small] tile={tile} r={[p['r'] for p in batch]}", flush=True)
-    res = ctx.residual_batched(batch, "fp64", tile)
+    print(f"[batched small] {strategy} tile={tile} r={[p['r'] for p in batch]}", flush=True)
+    res = ctx.residual_batched(batch, "fp64", tile, flags=STRATEGIES[strategy])
     for p, (Raa, Rab, n2) in zip(batch, res):
         check_oracle(p, Raa, Rab, n2, TOL64)
 
@@ -80,11 +85,12 @@ def test_small_batch_general_kernels(acse, ctx):
         check_oracle(p, Raa, Rab, n2, TOL64)
 
 
-def test_big_batch_equals_single_launches(ctx, big_batch):
+@pytest.mark.parametrize("strategy", list(STRATEGIES))
+def test_big_batch_equals_single_launches(ctx, big_batch, strategy):
     import torch
-    res = ctx.residual_batched(big_batch, "fp64", 1)
+    res = ctx.residual_batched(big_batch, "fp64", 1, flags=STRATEGIES[strategy])
     for i, (p, (Raa, Rab, n2)) in enumerate(zip(big_batch, res)):
-        print(f"[batched big] instance {i} r={p['r']}", flush=True)
+        print(f"[batched big] {strategy} instance {i} r={p['r']}", flush=True)
         Saa, Sab, s2 = ctx.residual(p["h"], p["V"], p["gamma"], p["d2aa"], p["d2ab"], p["N"] // 2,
                                     "fp64", 1)
         assert torch.equal(Raa, Saa) and torch.equal(Rab, Sab), i
@@ -93,9 +99,10 @@ def test_big_batch_equals_single_launches(ctx, big_batch):
             check_oracle(p, Raa, Rab, n2, TOL64)
 
 
-def test_big_batch_fp32(ctx, big_batch):
+@pytest.mark.parametrize("strategy", list(STRATEGIES))
+def test_big_batch_fp32(ctx, big_batch, strategy):
     sub = [p for p in big_batch if p["r"] == 20]
-    res = ctx.residual_batched(big_batch, "fp32")
+    res = ctx.residual_batched(big_batch, "fp32", flags=STRATEGIES[strategy])
     k = 0
     for p, (Raa, Rab, n2) in zip(big_batch, res):
         if p["r"] != 20:
@@ -112,14 +119,24 @@ def test_autotune_batched_and_reuse(acse, ctx, big_batch):
         prob, t = ctx.problem(p["h"], p["V"], p["gamma"], p["d2aa"], p["d2ab"], p["N"] // 2)
         probs.append(prob)
         keep.append(t)
-    best, times = ctx.autotune_batched_raw(probs, ctx.options("fp64"))
-    print(f"[batched autotune] best {best} times {times}", flush=True)
+    pers = acse.FLAG_BATCH_PERSISTENT
+    best, times = ctx.autotune_batched_raw(probs, ctx.options("fp64", flags=pers))
+    print(f"[batched autotune] persistent: best {best} times {times}", flush=True)
     assert 0 <= best < acse.NUM_TILE_CONFIGS and all(t > 0 for t in times)
-    # tuned configuration is used with tile = -1
-    tuned = ctx.residual_batched(big_batch, "fp64", -1)
-    fixed = ctx.residual_batched(big_batch, "fp64", best)
+    # the persistent launch takes the tuned configuration with tile = -1
+    tuned = ctx.residual_batched(big_batch, "fp64", -1, flags=pers)
+    fixed = ctx.residual_batched(big_batch, "fp64", best, flags=pers)
     for a, b in zip(tuned, fixed):
         assert torch.equal(a[0], b[0]) and torch.equal(a[1], b[1])
+    # lanes: every r tuned as a single call; tile = -1 then gives each
+    # instance's single-call result bitwise
+    best, times = ctx.autotune_batched_raw(probs, ctx.options("fp64"))
+    print(f"[batched autotune] lanes: best (r = 44) {best} times {times}", flush=True)
+    assert 0 <= best < acse.NUM_TILE_CONFIGS and all(t > 0 for t in times)
+    tuned = ctx.residual_batched(big_batch, "fp64", -1)
+    for p, (Raa, Rab, n2) in zip(big_batch, tuned):
+        Saa, Sab, s2 = ctx.residual(p["h"], p["V"], p["gamma"], p["d2aa"], p["d2ab"], p["N"] // 2, "fp64")
+        assert torch.equal(Raa, Saa) and torch.equal(Rab, Sab) and n2 == s2
     # a smaller batch afterwards reuses the workspace
     small = small_batch()[:3]
     for p, (Raa, Rab, n2) in zip(small, ctx.residual_batched(small, "fp64")):

@@ -153,7 +153,7 @@ def test_unknown_option_flags_rejected(acse, ctx):
     prob, keep = ctx.problem(p["h"], p["V"], p["gamma"], p["d2aa"], p["d2ab"], p["N"] // 2)
     out = [keep[3].clone(), keep[4].clone()]
     with pytest.raises(acse.AcseError, match="flags"):
-        ctx.residual_raw(prob, ctx.options("fp64", flags=4), out[0], out[1])
+        ctx.residual_raw(prob, ctx.options("fp64", flags=8), out[0], out[1])
 
 
 @pytest.mark.parametrize("r,N,active", [(2, 2, None), (3, 2, None), (3, 6, None), (5, 10, None),
