@@ -440,12 +440,16 @@ acse_status acse_residual_noalloc(void *hip_stream, const acse_problem *prob, co
  * The residual and update come in the same three blocks (R_aa, R_bb, R_ab with
  * R_ab = R(ia jb|ka lb)); ||R||^2 = ||R_aa||^2 + ||R_bb||^2 + 4 ||R_ab||^2 over
  * spin orbitals.  These calls run the spin-orbital map (Valdemoro 3-RDM) over
- * spatial spin blocks: 17 r^2 x r^2 x r^2 FP64 products per map.  Options:
- * precision ACSE_FP64 only, Valdemoro only, ACSE_FLAG_GENERAL_KERNELS allowed
+ * spatial spin blocks: 17 r^2 x r^2 x r^2 products per map, in FP64 or (with
+ * precision ACSE_INT8CRT, moduli as for the singlet calls) as int8
+ * exact-accumulation products of FP64 accuracy.  Options: precision ACSE_FP64
+ * or ACSE_INT8CRT, Valdemoro only, ACSE_FLAG_GENERAL_KERNELS allowed
  * (ACSE_FLAG_CHECK_INPUTS and the other precisions are ACSE_ERR_UNSUPPORTED);
- * tile as for acse_residual.  The first call allocates a workspace for r_max:
- * 48 r_max^4 doubles and 25 GEMM operand buffers (about 3.7 GB at
- * r_max = 50), kept until acse_destroy.  A singlet state given in this form
+ * tile as for acse_residual (FP64).  The first call allocates a workspace for
+ * r_max: 48 r_max^4 doubles and 25 GEMM operand buffers (about 3.7 GB at
+ * r_max = 50), kept until acse_destroy; the first ACSE_INT8CRT call adds the
+ * residues of those buffers and of one launch's products (about 3.0 GB at
+ * r_max = 50).  A singlet state given in this form
  * (d1b = d1a, d2bb = d2aa, d2ab pair-exchange symmetric) gives the singlet
  * calls' results. */
 typedef struct {

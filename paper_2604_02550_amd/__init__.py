@@ -476,12 +476,14 @@ class Context:
                                             _ptr(R_ab), ctypes.byref(n2) if want_norm else None))
         return n2.value
 
-    def residual_spin(self, h, V, d1a, d1b, d2aa, d2bb, d2ab, n_alpha, n_beta, tile=-1, flags=0):
-        """R_aa, R_bb, R_ab (device) and ||R||^2 of Eq. (4) for a state of any S_z."""
+    def residual_spin(self, h, V, d1a, d1b, d2aa, d2bb, d2ab, n_alpha, n_beta, tile=-1, flags=0,
+                      precision="fp64", moduli=0):
+        """R_aa, R_bb, R_ab (device) and ||R||^2 of Eq. (4) for a state of any S_z
+        (precision "fp64" or "int8crt")."""
         prob, keep = self.problem_spin(h, V, d1a, d1b, d2aa, d2bb, d2ab, n_alpha, n_beta)
         r = prob.r
         R = [torch.empty((r, r, r, r), dtype=torch.float64, device=self.device) for _ in range(3)]
-        n2 = self.residual_spin_raw(prob, self.options("fp64", None, tile, flags), *R)
+        n2 = self.residual_spin_raw(prob, self.options(precision, None, tile, flags, moduli=moduli), *R)
         return R[0], R[1], R[2], n2
 
     def step_spin_raw(self, prob, eps, opts, outs=(None,) * 6, want=True):
@@ -497,7 +499,7 @@ class Context:
         return e.value, n2.value
 
     def step_spin(self, h, V, d1a, d1b, d2aa, d2bb, d2ab, n_alpha, n_beta, eps=1e-3, active=None, tile=-1,
-                  return_ru=False, flags=0):
+                  return_ru=False, flags=0, precision="fp64", moduli=0):
         """One Euler step of Eq. (9) for a state of any S_z on device copies; a dict
         with the new d1a, d1b, d2aa, d2bb, d2ab, the energy after the step and
         ||R||^2 before it (and R, U blocks with return_ru)."""
@@ -506,7 +508,7 @@ class Context:
         outs = [None] * 6
         if return_ru:
             outs = [torch.empty((r, r, r, r), dtype=torch.float64, device=self.device) for _ in range(6)]
-        E, n2 = self.step_spin_raw(prob, eps, self.options("fp64", active, tile, flags), outs)
+        E, n2 = self.step_spin_raw(prob, eps, self.options(precision, active, tile, flags, moduli=moduli), outs)
         res = dict(d1a=t[2], d1b=t[3], d2aa=t[4], d2bb=t[5], d2ab=t[6], energy=E, norm2=n2)
         if return_ru:
             res.update(zip(("R_aa", "R_bb", "R_ab", "U_aa", "U_bb", "U_ab"), outs))

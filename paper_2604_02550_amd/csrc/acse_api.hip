@@ -2408,6 +2408,14 @@ struct SpinWs {
   double *R[3] = {}, *U[3] = {}, *Rm[3] = {};
   double *G2p[16] = {}, *Wp[16] = {}, *WPp[16] = {}, *XAp[16] = {}, *Hp[16] = {}, *XtP[16] = {};
   double *f[2] = {}, *t[2] = {}, *part = nullptr, *scal = nullptr;
+  double *ops[kSpinOps] = {};  // every GEMM operand buffer, in allocation order
+  // int8 exact-accumulation products (allocated by the first such call): the
+  // residue planes and row exponents of each operand buffer, and the residues
+  // of one launch's products
+  void *cbase = nullptr;
+  int8_t *cres[kSpinOps] = {};
+  int *cexp[kSpinOps] = {};
+  int8_t *cy = nullptr;
 };
 
 acse_status ensure_spin_ws(acse_ctx c, SpinWs *&out) {
@@ -2436,7 +2444,13 @@ acse_status ensure_spin_ws(acse_ctx c, SpinWs *&out) {
   for (int b : {B0000, B1111, B0101}) { w.Y[b] = take_nat(); w.S[b] = take_nat(); }
   for (int b : {B0000, B1111, B0101, B0110}) w.T[b] = take_nat();
   for (int k = 0; k < 3; ++k) { w.R[k] = take_nat(); w.U[k] = take_nat(); w.Rm[k] = take_nat(); }
-  auto take_op = [&]() { double *x = reinterpret_cast<double *>(q); q += opb; return x; };
+  int nops = 0;
+  auto take_op = [&]() {
+    double *x = reinterpret_cast<double *>(q);
+    q += opb;
+    w.ops[nops++] = x;
+    return x;
+  };
   for (int b : {B0000, B1111, B0101}) { w.G2p[b] = take_op(); w.Wp[b] = take_op(); w.XAp[b] = take_op(); }
   for (int b : kSix) { w.WPp[b] = take_op(); w.XtP[b] = take_op(); }
   for (int b : {B0000, B1111, B0101, B1001}) w.Hp[b] = take_op();
@@ -2466,8 +2480,14 @@ acse_status validate_spin(acse_ctx c, const acse_problem_spin *p, const acse_opt
     if (!aligned16(ptrs[k])) return fail(c, ACSE_ERR_ALIGN, "problem arrays must be 16-byte aligned");
   }
   if (o) {
-    if (o->precision != ACSE_FP64)
-      return fail(c, ACSE_ERR_UNSUPPORTED, "the spin-block path runs its products in FP64 only");
+    if (o->precision < ACSE_FP64 || o->precision > ACSE_INT8CRT)
+      return fail(c, ACSE_ERR_ARG, "unknown precision");
+    if (o->precision != ACSE_FP64 && o->precision != ACSE_INT8CRT)
+      return fail(c, ACSE_ERR_UNSUPPORTED, "the spin-block path runs its products in FP64 or int8 exact "
+                                           "accumulation only");
+    if (o->moduli != 0 && (o->moduli < kMinModuli || o->moduli > kMaxModuli))
+      return fail(c, ACSE_ERR_ARG, "moduli must be 0 or in [" + std::to_string(kMinModuli) + ", " +
+                                       std::to_string(kMaxModuli) + "]");
     if (o->reconstruction != ACSE_RECON_V)
       return fail(c, ACSE_ERR_UNSUPPORTED, "the spin-block path takes the Valdemoro reconstruction only");
     if (o->flags & ~ACSE_FLAG_GENERAL_KERNELS)
@@ -2479,7 +2499,72 @@ acse_status validate_spin(acse_ctx c, const acse_problem_spin *p, const acse_opt
   }
   c->general = o && (o->flags & ACSE_FLAG_GENERAL_KERNELS);
   c->ny_on = false;
-  c->crt_moduli = 0;
+  c->crt_moduli = (o && o->precision == ACSE_INT8CRT) ? (o->moduli ? o->moduli : kDefaultModuli) : 0;
+  return ACSE_OK;
+}
+
+// Residue workspace of the spin-block products (first int8 call) and the
+// moduli table of the call in progress.
+acse_status ensure_spin_crt(acse_ctx c, SpinWs &w) {
+  if (!w.cbase) {
+    const int rm = c->r_max;
+    const int64_t r2 = (int64_t)rm * rm;
+    const int64_t rbytes = round_up((int64_t)kMaxModuli * op_rows(rm) * crt_ldr((int)r2), 256);
+    const int64_t ebytes = round_up(op_rows(rm) * (int64_t)sizeof(int), 256);
+    const int64_t ybytes = round_up(6 * (int64_t)kMaxModuli * crt_residue_out_bytes((int)r2, (int)r2), 256);
+    const int64_t bytes = kSpinOps * (rbytes + ebytes) + ybytes;
+    if (hipMalloc(&w.cbase, bytes) != hipSuccess) {
+      (void)hipGetLastError();
+      w.cbase = nullptr;
+      return fail(c, ACSE_ERR_NOMEM, "cannot allocate the int8 residue workspace of the spin-block path (" +
+                                         std::to_string(bytes) + " bytes)");
+    }
+    char *q = static_cast<char *>(w.cbase);
+    for (int k = 0; k < kSpinOps; ++k) {
+      w.cres[k] = reinterpret_cast<int8_t *>(q);
+      q += rbytes;
+      w.cexp[k] = reinterpret_cast<int *>(q);
+      q += ebytes;
+    }
+    w.cy = reinterpret_cast<int8_t *>(q);
+  }
+  if (c->crt.nmod != c->crt_moduli && !crt_table(c->crt_moduli, c->crt))
+    return fail(c, ACSE_ERR_ARG, "no moduli table for " + std::to_string(c->crt_moduli) + " moduli");
+  return ACSE_OK;
+}
+
+int spin_op_index(const SpinWs &w, const double *op) {
+  for (int k = 0; k < kSpinOps; ++k)
+    if (w.ops[k] == op) return k;
+  return -1;
+}
+
+// FP64 spin operands ([r^2 rows][ld], K = r^2) -> residue planes and row
+// exponents; premul for the operands built from the 2-RDM (one per product).
+acse_status spin_residues(acse_ctx c, SpinWs &w, int r, const std::vector<const double *> &ops, bool premul) {
+  const int r2 = r * r;
+  for (size_t first = 0; first < ops.size(); first += kMaxResidueJobs) {
+    ResidueBatch b{};
+    int rows = 0;
+    for (size_t q = first; q < ops.size() && b.count < kMaxResidueJobs; ++q) {
+      const int k = spin_op_index(w, ops[q]);
+      if (k < 0) return fail(c, ACSE_ERR_HIP, "internal: unknown spin operand buffer");
+      ResidueJob &J = b.job[b.count++];
+      J.src = ops[q];
+      J.dst = w.cres[k];
+      J.e = w.cexp[k];
+      J.plane = op_rows(r) * crt_ldr(r2);
+      J.row_begin = rows;
+      J.K = r2;
+      J.ld = (int)op_ld(r);
+      J.ldr = (int)crt_ldr(r2);
+      J.kbits = crt_kbits(c->crt, r2);
+      J.premul = premul ? 1 : 0;
+      rows += r2;
+    }
+    b.total_rows = rows;
+    HIP_TRY(c, launch_to_residues(b, c->crt, c->stream));
+  }
   return ACSE_OK;
 }
 
@@ -2524,6 +2609,14 @@ acse_status spin_prep(acse_ctx c, SpinWs &w, const acse_problem_spin *p) {
   HIP_TRY(c, pack1(w.G2p[B0101], p->d2ab, 2.0, 0, 1, 2, 3));
   for (int b : {B0000, B1111, B0101}) HIP_TRY(c, pack1(w.Wp[b], w.W[b], 1.0, 0, 1, 2, 3));
   for (int b : kSix) HIP_TRY(c, pack1(w.WPp[b], w.W[b], 1.0, 0, 3, 1, 2));
+  if (c->crt_moduli) {
+    acse_status st = ensure_spin_crt(c, w);
+    if (st != ACSE_OK) return st;
+    std::vector<const double *> ops;
+    for (int b : {B0000, B1111, B0101}) { ops.push_back(w.G2p[b]); ops.push_back(w.Wp[b]); }
+    for (int b : kSix) ops.push_back(w.WPp[b]);
+    return spin_residues(c, w, r, ops, true);
+  }
   return ACSE_OK;
 }
 
@@ -2615,10 +2708,19 @@ acse_status spin_map(acse_ctx c, SpinWs &w, int r, const double *ga, const doubl
     for (int b : {B0000, B1111, B0101}) HIP_TRY(c, pack1(w.XAp[b], w.XA[b], 0, 1, 2, 3));
     for (int b : {B0000, B1111, B0101, B1001}) HIP_TRY(c, pack1(w.Hp[b], w.H[b], 0, 1, 2, 3));
     for (int b : kSix) HIP_TRY(c, pack1(w.XtP[b], w.Xt[b], 0, 2, 1, 3));  // rows (k,i), K (p,s)
+    if (c->crt_moduli) {
+      std::vector<const double *> ops;
+      for (int b : {B0000, B1111, B0101}) ops.push_back(w.XAp[b]);
+      for (int b : {B0000, B1111, B0101, B1001}) ops.push_back(w.Hp[b]);
+      for (int b : kSix) ops.push_back(w.XtP[b]);
+      acse_status st = spin_residues(c, w, r, ops, false);
+      if (st != ACSE_OK) return st;
+    }
   }
-  // the 17 products
+  // the 17 products in three launches of 6, 6 and 5; the second E term of the
+  // four blocks that have one accumulates in the last launch, after the
+  // launch that wrote the first
   {
-    StageTimer t3(c, 3);
     const int kp = gemm_kp(GEMM_F64, (int)r2, ld);
     auto prob = [&](GemmProb &P, const double *A, const double *B, double alpha, double *C, bool ph, int acc) {
       P = GemmProb{};
@@ -2629,33 +2731,71 @@ acse_status spin_map(acse_ctx c, SpinWs &w, int r, const double *ga, const doubl
       P.ksplit = 1; P.kchunk = kp; P.accumulate = acc;
     };
     const int cfg = map_cfg(c, GEMM_F64, r, -1);
+    // FP64 products, or the int8 exact-accumulation ones from the residues of
+    // the same operand buffers (the reconstruction writes through the same
+    // store maps)
+    auto launch = [&](GemmBatch &b) -> acse_status {
+      if (!c->crt_moduli) {
+        StageTimer t3(c, 3);
+        HIP_TRY(c, gemm_launch(GEMM_F64, cfg, b, s));
+        return ACSE_OK;
+      }
+      const int r2i = (int)r2;
+      const int64_t plane = op_rows(r) * crt_ldr(r2i);
+      int64_t yoff = 0;
+      for (int q = 0; q < b.count; ++q) {
+        GemmProb &P = b.p[q];
+        const int ka = spin_op_index(w, static_cast<const double *>(P.A));
+        const int kb = spin_op_index(w, static_cast<const double *>(P.B));
+        if (ka < 0 || kb < 0) return fail(c, ACSE_ERR_HIP, "internal: unknown spin operand buffer");
+        P.A = w.cres[ka];
+        P.B = w.cres[kb];
+        P.ld = P.Kp = (int)crt_ldr(r2i);
+        P.plane_a = P.plane_b = plane;
+        P.ea = w.cexp[ka];
+        P.eb = w.cexp[kb];
+        P.kshift = 2 * crt_kbits(c->crt, r2i);
+        P.Y = w.cy + yoff;
+        P.plane_y = crt_residue_out_bytes(P.M, P.N);
+        yoff += (int64_t)c->crt.nmod * P.plane_y;
+      }
+      {
+        StageTimer t3(c, 3);
+        HIP_TRY(c, gemm_crt_launch(b, c->crt, s));
+      }
+      StageTimer t4(c, 4);
+      HIP_TRY(c, crt_combine_launch(b, c->crt, s));
+      return ACSE_OK;
+    };
+    acse_status st;
     GemmBatch b1{};
-    b1.count = 7;
+    b1.count = 6;
     prob(b1.p[0], w.G2p[B0000], w.XAp[B0000], 1.0, w.Y[B0000], false, 0);
     prob(b1.p[1], w.G2p[B1111], w.XAp[B1111], 1.0, w.Y[B1111], false, 0);
     prob(b1.p[2], w.G2p[B0101], w.XAp[B0101], 2.0, w.Y[B0101], false, 0);
     prob(b1.p[3], w.Wp[B0000], w.Hp[B0000], 1.0, w.T[B0000], false, 0);
     prob(b1.p[4], w.Wp[B1111], w.Hp[B1111], 1.0, w.T[B1111], false, 0);
     prob(b1.p[5], w.Wp[B0101], w.Hp[B0101], 2.0, w.T[B0101], false, 0);
-    prob(b1.p[6], w.Wp[B0101], w.Hp[B1001], 2.0, w.T[B0110], false, 0);
-    HIP_TRY(c, gemm_launch(GEMM_F64, cfg, b1, s));
-    // E^{ij}_{kl} = 2 sum Xt^{kp}_{is} W^{jp}_{sl}: first terms, then the second ones
+    if ((st = launch(b1)) != ACSE_OK) return st;
+    // E^{ij}_{kl} = 2 sum Xt^{kp}_{is} W^{jp}_{sl}: the first terms of the four
+    // blocks with two, then the rest
     GemmBatch b2{};
     b2.count = 6;
-    prob(b2.p[0], w.XtP[B0000], w.WPp[B0000], 2.0, w.E[B0000], true, 0);
-    prob(b2.p[1], w.XtP[B1111], w.WPp[B1111], 2.0, w.E[B1111], true, 0);
-    prob(b2.p[2], w.XtP[B0000], w.WPp[B1001], 2.0, w.E[B0101], true, 0);
-    prob(b2.p[3], w.XtP[B0110], w.WPp[B0101], 2.0, w.E[B1001], true, 0);
-    prob(b2.p[4], w.XtP[B1001], w.WPp[B1010], 2.0, w.E[B0110], true, 0);
-    prob(b2.p[5], w.XtP[B1010], w.WPp[B0000], 2.0, w.E[B1010], true, 0);
-    HIP_TRY(c, gemm_launch(GEMM_F64, cfg, b2, s));
+    prob(b2.p[0], w.Wp[B0101], w.Hp[B1001], 2.0, w.T[B0110], false, 0);
+    prob(b2.p[1], w.XtP[B0000], w.WPp[B0000], 2.0, w.E[B0000], true, 0);
+    prob(b2.p[2], w.XtP[B1111], w.WPp[B1111], 2.0, w.E[B1111], true, 0);
+    prob(b2.p[3], w.XtP[B0000], w.WPp[B1001], 2.0, w.E[B0101], true, 0);
+    prob(b2.p[4], w.XtP[B1010], w.WPp[B0000], 2.0, w.E[B1010], true, 0);
+    prob(b2.p[5], w.XtP[B0110], w.WPp[B0101], 2.0, w.E[B1001], true, 0);
+    if ((st = launch(b2)) != ACSE_OK) return st;
     GemmBatch b3{};
-    b3.count = 4;
-    prob(b3.p[0], w.XtP[B0101], w.WPp[B0110], 2.0, w.E[B0000], true, 1);
-    prob(b3.p[1], w.XtP[B1010], w.WPp[B1001], 2.0, w.E[B1111], true, 1);
-    prob(b3.p[2], w.XtP[B0101], w.WPp[B1111], 2.0, w.E[B0101], true, 1);
-    prob(b3.p[3], w.XtP[B1111], w.WPp[B0110], 2.0, w.E[B1010], true, 1);
-    HIP_TRY(c, gemm_launch(GEMM_F64, cfg, b3, s));
+    b3.count = 5;
+    prob(b3.p[0], w.XtP[B1001], w.WPp[B1010], 2.0, w.E[B0110], true, 0);
+    prob(b3.p[1], w.XtP[B0101], w.WPp[B0110], 2.0, w.E[B0000], true, 1);
+    prob(b3.p[2], w.XtP[B1010], w.WPp[B1001], 2.0, w.E[B1111], true, 1);
+    prob(b3.p[3], w.XtP[B0101], w.WPp[B1111], 2.0, w.E[B0101], true, 1);
+    prob(b3.p[4], w.XtP[B1111], w.WPp[B0110], 2.0, w.E[B1010], true, 1);
+    if ((st = launch(b3)) != ACSE_OK) return st;
   }
   StageTimer t4(c, 4);
   // T += 2 sum_s f_ks W^{ij}_{sl} (index 2 of W keeps its spin)
@@ -2836,7 +2976,9 @@ extern "C" acse_status acse_step_spin(acse_ctx ctx, acse_problem_spin *prob, dou
 
 namespace {
 void release_spin_ws(acse_ctx c) {
-  delete static_cast<SpinWs *>(c->spws);
+  SpinWs *w = static_cast<SpinWs *>(c->spws);
+  if (w && w->cbase) (void)hipFree(w->cbase);
+  delete w;
   c->spws = nullptr;
 }
 }  // namespace

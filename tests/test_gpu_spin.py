@@ -169,6 +169,8 @@ def test_spin_step_identities_and_errors(acse, ctx):
     with pytest.raises(acse.AcseError, match="UNSUPPORTED"):
         ctx.residual_spin_raw(prob, ctx.options("fp32"), *R)
     with pytest.raises(acse.AcseError, match="UNSUPPORTED"):
+        ctx.residual_spin_raw(prob, ctx.options("bf16x3"), *R)
+    with pytest.raises(acse.AcseError, match="UNSUPPORTED"):
         ctx.residual_spin_raw(prob, ctx.options(sigma=True), *R)
     singlet, _ = ctx.problem(p["h"], p["V"], p["gamma_a"], p["d2aa"], p["d2ab"], p["Na"], n_beta=p["Nb"])
     with pytest.raises(acse.AcseError, match="_spin calls"):
@@ -203,5 +205,64 @@ def test_r50_spin_step_vs_stored_oracle(acse):
         assert abs(out["energy"] - g["energy1"]) < 1e-7
         for k, ok in (("d1a", "gamma_a"), ("d1b", "gamma_b")):
             assert np.abs(cpu(out[k]) - np.array(g[ok])).max() <= TOL, k
+    finally:
+        ctx.close()
+
+
+@pytest.mark.parametrize("name", ["fock_triplet_r4", "det_sz1_r4", "r9_5_4", "r16_9_6", "r24_14_10"])
+def test_spin_int8crt_residual_and_step(ctx, name):
+    """The int8 exact-accumulation products on the spin-block path: the same
+    FP64 bar against the oracle (the products are exact for operands rounded
+    to k = 44+ bits)."""
+    p = PROBLEMS[name]()
+    print(f"[spin int8crt] {name}", flush=True)
+    raa, rbb, rab, n2 = ost.residual_spin(*_oracle_args(p))
+    Raa, Rbb, Rab, gn2 = ctx.residual_spin(*_args(p), precision="int8crt")
+    _check_blocks(dict(R_aa=Raa, R_bb=Rbb, R_ab=Rab), dict(R_aa=raa, R_bb=rbb, R_ab=rab), ("R_aa", "R_bb", "R_ab"))
+    assert abs(gn2 - n2) <= TOL * n2
+    o = ost.step_spin(*_oracle_args(p), 1e-3)
+    g = ctx.step_spin(*_args(p), eps=1e-3, return_ru=True, precision="int8crt")
+    for keys in (("R_aa", "R_bb", "R_ab"), ("U_aa", "U_bb", "U_ab"), ("d2aa", "d2bb", "d2ab")):
+        _check_blocks(g, o, keys)
+    assert abs(g["energy"] - o["energy"]) <= TOL * max(1.0, abs(o["energy"]))
+
+
+def test_spin_int8crt_moduli_and_masked_step(acse, ctx):
+    """Fewer moduli (fewer operand bits) raise the error as 2^-k; a masked
+    int8 step matches the oracle."""
+    p = PROBLEMS["r13_8_5"]()
+    raa, rbb, rab, n2 = ost.residual_spin(*_oracle_args(p))
+    errs = []
+    for m in (8, 10, 13):
+        Raa, Rbb, Rab, gn2 = ctx.residual_spin(*_args(p), precision="int8crt", moduli=m)
+        errs.append(max(np.abs(cpu(x) - y).max() for x, y in ((Raa, raa), (Rbb, rbb), (Rab, rab))))
+    print(f"[spin int8crt] max errors for 8, 10, 13 moduli: {errs}", flush=True)
+    assert errs[0] > errs[1] > errs[2]
+    assert errs[2] <= TOL * max(np.abs(raa).max(), np.abs(rab).max())
+    act = np.zeros(13, bool)
+    act[[0, 3, 4, 9]] = True
+    o = ost.step_spin(*_oracle_args(p), 1e-3, active=act)
+    g = ctx.step_spin(*_args(p), eps=1e-3, active=act, return_ru=True, precision="int8crt")
+    for keys in (("R_aa", "R_bb", "R_ab"), ("U_aa", "U_bb", "U_ab"), ("d2aa", "d2bb", "d2ab")):
+        _check_blocks(g, o, keys)
+
+
+def test_r50_spin_int8crt_step_vs_stored_oracle(acse):
+    """Full size in the int8 mode: the stored oracle step at 1e-10 and
+    |dE| < 1e-7 Eh."""
+    g = json.load(open(SPIN_GOLDEN))
+    p = gen.named_spin(g["workload"])
+    print("[spin fullsize] r50s int8crt step", flush=True)
+    ctx = acse.Context(r_max=50)
+    try:
+        out = ctx.step_spin(*_args(p), eps=g["eps"], return_ru=True, precision="int8crt")
+        idx = tuple(np.array(g["index"]).T)
+        for k in g["samples"]:
+            got = cpu(out[k])
+            ref = np.array(g["samples"][k])
+            assert np.abs(got[idx] - ref).max() <= TOL * np.abs(ref).max(), k
+            assert abs(np.linalg.norm(got) - g["norms"][k]) <= TOL * g["norms"][k], k
+        assert abs(out["norm2"] - g["norm2"]) <= TOL * g["norm2"]
+        assert abs(out["energy"] - g["energy1"]) < 1e-7
     finally:
         ctx.close()
