@@ -285,13 +285,15 @@ def bench_ny(acse, ctx, prob, work, pristine, torch, stream, steps, warmup, eps,
     ny_ms = prof["ny_share"][0] / steps
     gemm_ms = prof["ny_gemm"][0] / steps
     flops = 2 * ny_map_flops(r)
-    achieved = flops / (gemm_ms * 1e-3) / 1e12
+    work = flops * (CRT_MODULI if mode == "int8crt" else 1)   # int8 ops: one product per modulus
+    achieved = work / (gemm_ms * 1e-3) / 1e12
     return dict(ms_per_step=ms, steps_per_s=1e3 / ms, over_valdemoro_step=ms / v_step_ms,
                 residual_ms=res_ms, residual_evals_per_s=1e3 / res_ms,
                 stage_ms_per_step={k: v[0] / steps for k, v in prof.items()},
                 ny_share_ms_per_step=ny_ms, ny_block_gemm_flops_per_step=flops,
                 ny_share_tflops=flops / (ny_ms * 1e-3) / 1e12,
-                roofline={"bound": "mfma", "achieved": achieved, "peak": PEAK_TFLOPS[mode], "unit": "TFLOP/s",
+                roofline={"bound": "mfma", "achieved": achieved, "peak": PEAK_TFLOPS[mode],
+                          "unit": "TOP/s" if mode == "int8crt" else "TFLOP/s",
                           "frac": achieved / PEAK_TFLOPS[mode],
                           "kernel": "gemm_nt_kernel on the NY block products (18 per map, one with its summed pair packed; "
                                     "HIP-event time of their launches)"},
@@ -611,11 +613,10 @@ def main():
         line["solve"] = bench_solve(acse, ctx, prob, work, pristine, torch, args.solve_controls.split(","),
                                     args.solve_iters, args.solve_eps, results.get("fp64", hr)["ms_per_step"])
     if args.ny_steps > 0:
-        # NY runs its block products in FP64, FP32 or split BF16 (not int8crt)
         line["nakatsuji_yasuda"] = {
             mode: bench_ny(acse, ctx, prob, work, pristine, torch, stream, args.ny_steps, min(args.warmup, 2),
                            args.eps, results[mode]["ms_per_step"], mode)
-            for mode in args.modes.split(",") if mode != "int8crt"}
+            for mode in args.modes.split(",")}
     if args.spin_steps > 0:
         line["non_singlet"] = {m: bench_spin(acse, ctx, gen, torch, args.spin_steps, min(args.warmup, 2), args.eps, m)
                                for m in ("int8crt", "fp64")}

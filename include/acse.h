@@ -89,18 +89,21 @@ typedef enum {
                       K 2^(2k) < M/4; k = 44 for 13 moduli at K = 2500), the integers are
                       split into their residues modulo `moduli` pairwise coprime moduli
                       <= 256, each modulus runs one int8 product with exact int32
-                      accumulation (v_mfma_i32_16x16x64_i8), and the exact integer
+                      accumulation (v_mfma_i32_32x32x32_i8), and the exact integer
                       product is rebuilt by the Chinese remainder theorem in FP64.  The
                       only rounding is that of the operands to k bits relative to their
                       row's largest magnitude.  Residual, update map, step, autotune
-                      and the Euler iteration (fixed and backtracking controls); the
-                      adjoint, the quadratic control, the batched residual, the NY
-                      reconstruction and acse_residual_noalloc are
-                      ACSE_ERR_UNSUPPORTED with it.  The first call allocates residue
-                      buffers for r_max: 12 x (15 x op_rows x round_up(r_max^2, 256) +
-                      4 op_rows) bytes for the operands (op_rows = r_max^2 rounded up to
-                      256) and 15 x about 4.5 r_max^4 bytes for the products' residues
-                      (1.6 GB in all at r_max = 50). */
+                      and the Euler iteration (fixed and backtracking controls), with
+                      the Valdemoro or the NY reconstruction, and the spin-block calls;
+                      the adjoint, the quadratic control, the batched residual and
+                      acse_residual_noalloc are ACSE_ERR_UNSUPPORTED with it.  The first
+                      call allocates residue buffers for r_max: 12 x (15 x op_rows x
+                      round_up(r_max^2, 256) + 4 op_rows) bytes for the operands
+                      (op_rows = r_max^2 rounded up to 256) and 15 x about 4.5 r_max^4
+                      bytes for the products' residues (1.6 GB in all at r_max = 50);
+                      the first NY call in this mode adds the residues of the NY
+                      operand buffers and of six block products (about 0.1 GB per
+                      operand buffer and 0.6 GB at r_max = 50). */
 } acse_precision;
 
 typedef struct {

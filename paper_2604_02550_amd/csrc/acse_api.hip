@@ -106,6 +106,11 @@ struct acse_ctx_s {
   acse::ny::Plan ny_plan;
   bool ny_planned = false;
   void *nybase = nullptr;
+  // residues of the NY operand buffers for the int8 products (first such call)
+  void *nycbase = nullptr;
+  std::vector<int8_t *> ny_cres;
+  std::vector<int *> ny_cexp;
+  int8_t *ny_cy = nullptr;
   int64_t nybytes = 0;
   int ny_r = 0;                     // r the operand buffers were last cleared for
   // set by acse_step around its update map: the 2-RDM has not changed since
@@ -264,9 +269,6 @@ acse_status validate(acse_ctx c, const acse_problem *p, const acse_options *o, b
     if (o->moduli != 0 && (o->moduli < kMinModuli || o->moduli > kMaxModuli))
       return fail(c, ACSE_ERR_ARG, "moduli must be 0 or in [" + std::to_string(kMinModuli) + ", " +
                                        std::to_string(kMaxModuli) + "]");
-    if (o->precision == ACSE_INT8CRT && o->reconstruction == ACSE_RECON_NY)
-      return fail(c, ACSE_ERR_UNSUPPORTED, "the int8 exact-accumulation products are built for the Valdemoro "
-                                           "reconstruction only");
     if (o->tile < -1 || o->tile >= gemm_num_tiles(GEMM_F64))
       return fail(c, ACSE_ERR_ARG, "tile configuration out of range");
     if (o->flags & ~(ACSE_FLAG_GENERAL_KERNELS | ACSE_FLAG_CHECK_INPUTS | ACSE_FLAG_BATCH_PERSISTENT))
@@ -633,6 +635,39 @@ acse_status ensure_ny_ws(acse_ctx c) {
 acse_status ny_share_run(acse_ctx c, const acse_problem *p, GemmPrec prec, int tile, const double *Xaa,
                          const double *Xab, double *Saa, double *Sab);
 
+// Residue planes and row exponents of every NY operand buffer, and the
+// residues of one launch's products, for the int8 products (first such call).
+acse_status ensure_ny_crt(acse_ctx c) {
+  if (!c->nycbase) {
+    const int rm = c->r_max;
+    const int nb = c->ny_plan.num_bufs;
+    const int64_t r2 = (int64_t)rm * rm;
+    const int64_t rbytes = round_up((int64_t)kMaxModuli * op_rows(rm) * crt_ldr((int)r2), 256);
+    const int64_t ebytes = round_up(op_rows(rm) * (int64_t)sizeof(int), 256);
+    const int64_t ybytes = round_up(6 * (int64_t)kMaxModuli * crt_residue_out_bytes((int)r2, (int)r2), 256);
+    const int64_t bytes = nb * (rbytes + ebytes) + ybytes;
+    if (hipMalloc(&c->nycbase, bytes) != hipSuccess) {
+      (void)hipGetLastError();
+      c->nycbase = nullptr;
+      return fail(c, ACSE_ERR_NOMEM, "cannot allocate the int8 residue workspace of the NY share (" +
+                                         std::to_string(bytes) + " bytes)");
+    }
+    char *q = static_cast<char *>(c->nycbase);
+    c->ny_cres.assign(nb, nullptr);
+    c->ny_cexp.assign(nb, nullptr);
+    for (int k = 0; k < nb; ++k) {
+      c->ny_cres[k] = reinterpret_cast<int8_t *>(q);
+      q += rbytes;
+      c->ny_cexp[k] = reinterpret_cast<int *>(q);
+      q += ebytes;
+    }
+    c->ny_cy = reinterpret_cast<int8_t *>(q);
+  }
+  if (c->crt.nmod != c->crt_moduli && !crt_table(c->crt_moduli, c->crt))
+    return fail(c, ACSE_ERR_ARG, "no moduli table for " + std::to_string(c->crt_moduli) + " moduli");
+  return ACSE_OK;
+}
+
 // The NY share of F(X): S_aa -= C_aa, S_ab -= C_ab (C = B - B(k<->l), B the
 // 3-cumulant's share of the 3-RDM contraction), on the plan of ny_plan.h.  No
 // C++ exception (an allocation of the plan's containers, a plan lookup)
@@ -653,6 +688,11 @@ acse_status ny_share_run(acse_ctx c, const acse_problem *p, GemmPrec prec, int t
   StageTimer t6(c, 6);
   acse_status st = ensure_ny_ws(c);
   if (st != ACSE_OK) return st;
+  // int8 exact accumulation: operands built in FP64, then converted to
+  // residues; the products' residues carry the reconstruction factors (u_out)
+  const bool crt = prec == GEMM_I8CRT;
+  if (crt && (st = ensure_ny_crt(c)) != ACSE_OK) return st;
+  if (crt) prec = GEMM_F64;
   const ny::Plan &P = c->ny_plan;
   NyPtrs q = ny_carve(c, r);
   const int64_t ld = op_ld(r), rows = op_rows(r), r2 = (int64_t)r * r;
@@ -736,18 +776,55 @@ acse_status ny_share_run(acse_ctx c, const acse_problem *p, GemmPrec prec, int t
       }
       HIP_TRY(c, launch_permute4(prec, a, opref(o.buf), s));
     }
+    // int8 products: the residues of every operand buffer this phase reads
+    // (K = r^2, or the r(r-1)/2 pairs of a packed operand)
+    std::vector<int> buf_packed(P.num_bufs, 0);
+    for (const ny::OperandBuild &o : P.operands) buf_packed[o.buf] = o.packed;
+    auto kdim = [&](int buf) { return buf_packed[buf] ? npair_lt(r) : (int)r2; };
+    if (crt) {
+      std::vector<char> used(P.num_bufs, 0);
+      for (const ny::Product &g : P.products)
+        if (g.phase == phase) used[g.a_buf] = used[g.b_buf] = 1;
+      ResidueBatch rb{};
+      int nrows = 0;
+      for (int id = 0; id <= P.num_bufs; ++id) {
+        if (id == P.num_bufs || rb.count == kMaxResidueJobs) {
+          if (rb.count) {
+            rb.total_rows = nrows;
+            HIP_TRY(c, launch_to_residues(rb, c->crt, s));
+          }
+          rb = ResidueBatch{};
+          nrows = 0;
+          if (id == P.num_bufs) break;
+        }
+        if (!used[id]) continue;
+        const int K = kdim(id);
+        ResidueJob &J = rb.job[rb.count++];
+        J.src = q.buf[id];
+        J.dst = c->ny_cres[id];
+        J.e = c->ny_cexp[id];
+        J.plane = rows * crt_ldr(K);
+        J.row_begin = nrows;
+        J.K = K;
+        J.ld = buf_packed[id] ? (int)ld_lt : (int)ld;
+        J.ldr = (int)crt_ldr(K);
+        J.kbits = crt_kbits(c->crt, K);
+        J.premul = 0;
+        nrows += (int)r2;
+      }
+    }
     // products: the t-th terms of all output blocks of the phase go out
-    // together (distinct outputs), up to kMaxGemmProbs a launch (timed as
-    // their own stage)
-    StageTimer t7(c, 7);
+    // together (distinct outputs), up to kMaxGemmProbs a launch (6 for the
+    // int8 products; timed as their own stage)
+    const size_t per_launch = crt ? 6 : kMaxGemmProbs;
     for (int term = 0;; ++term) {
       std::vector<const ny::Product *> round;
       for (const ny::Product &g : P.products)
         if (g.phase == phase && g.term == term) round.push_back(&g);
       if (round.empty()) break;
-      for (size_t b0 = 0; b0 < round.size(); b0 += kMaxGemmProbs) {
+      for (size_t b0 = 0; b0 < round.size(); b0 += per_launch) {
         GemmBatch batch{};
-        batch.count = (int)std::min<size_t>(kMaxGemmProbs, round.size() - b0);
+        batch.count = (int)std::min<size_t>(per_launch, round.size() - b0);
         for (int k = 0; k < batch.count; ++k) {
           const ny::Product &g = *round[b0 + k];
           int64_t os[4];
@@ -763,11 +840,29 @@ acse_status ny_share_run(acse_ctx c, const acse_problem *p, GemmPrec prec, int t
           G.ld = g.packed ? (int)ld_lt : (int)ld;
           G.sm1 = os[0]; G.sm0 = os[1]; G.sn1 = os[2]; G.sn0 = os[3];
           G.ksplit = 1; G.kchunk = G.Kp; G.accumulate = g.accumulate;
+          if (crt) {
+            const int K = kdim(g.a_buf);
+            G.A = c->ny_cres[g.a_buf];
+            G.B = c->ny_cres[g.b_buf];
+            G.A2 = G.B2 = nullptr;
+            G.ld = G.Kp = (int)crt_ldr(K);
+            G.kchunk = G.Kp;
+            G.plane_a = G.plane_b = rows * crt_ldr(K);
+            G.ea = c->ny_cexp[g.a_buf];
+            G.eb = c->ny_cexp[g.b_buf];
+            G.kshift = 2 * crt_kbits(c->crt, K);
+            G.u_out = 1;
+            G.plane_y = crt_residue_out_bytes(G.M, G.N);
+            G.Y = c->ny_cy + (int64_t)k * c->crt.nmod * G.plane_y;
+          }
         }
-        HIP_TRY(c, gemm_launch(prec, cfg, batch, s));
+        {
+          StageTimer t7(c, 7);  // the block products alone (int8: the modular products)
+          HIP_TRY(c, crt ? gemm_crt_launch(batch, c->crt, s) : gemm_launch(prec, cfg, batch, s));
+        }
+        if (crt) HIP_TRY(c, crt_combine_launch(batch, c->crt, s));
       }
     }
-    t7.stop();
     for (const ny::Unscramble &u : P.unscrambles) {
       if (u.phase != phase) continue;
       if (ny::is_product(u.out)) {
@@ -986,6 +1081,7 @@ acse_status acse_destroy(acse_ctx ctx) {
   if (ctx->nybase) (void)hipFree(ctx->nybase);
   if (ctx->cbase) (void)hipFree(ctx->cbase);
   if (ctx->spbase) (void)hipFree(ctx->spbase);
+  if (ctx->nycbase) (void)hipFree(ctx->nycbase);
   release_spin_ws(ctx);
   if (ctx->bbase) (void)hipFree(ctx->bbase);
   if (ctx->hdesc) (void)hipHostFree(ctx->hdesc);

@@ -35,11 +35,13 @@ struct GemmProb {
   int accumulate;     // 1: C += alpha * AB^T
   // exact-accumulation int8 products only (gemm_crt.hip): residue planes of A
   // and B lie plane_a / plane_b bytes apart, ea / eb are the row exponents
-  // and kshift the total scaling bits 2k
+  // and kshift the total scaling bits 2k; u_out: neither operand carries the
+  // reconstruction factors u_j, the product's residues are multiplied by them
   const int *ea;
   const int *eb;
   int64_t plane_a, plane_b;
   int kshift;
+  int u_out;
   int8_t *Y;          // residues of the product per modulus: plane j at Y + j * plane_y,
   int64_t plane_y;    // rows grouped by four: byte (m / 4, n, m % 4)
 };

@@ -8,10 +8,11 @@
 //      (rounding to nearest; the only inexact step), likewise B;
 //   2. the integers are reduced modulo pairwise coprime moduli m_j <= 256,
 //      each residue in the int8 range; one operand carries the factor
-//      u_j = (M/m_j)^-1 mod m_j (M = prod m_j);
+//      u_j = (M/m_j)^-1 mod m_j (M = prod m_j), or (u_out) the product's
+//      residues are multiplied by it;
 //   3. one int8 MFMA product per modulus, accumulated exactly in int32
 //      (|sum| <= K 128^2 < 2^31 for K < 131072), reduced to a residue
-//      y_j = acc_j mod m_j in the int8 range and stored;
+//      y_j = acc_j mod m_j (times u_j with u_out) in the int8 range and stored;
 //   4. sum_j (M/m_j) y_j = A_int B_int^T (mod M); with K 2^(2k) < M/4 the
 //      representative of smallest magnitude is the exact integer product;
 //   5. C = alpha * that integer * 2^(ea[m] + eb[n] - 2k), written through the
@@ -178,6 +179,7 @@ __device__ __forceinline__ void mod_tile(const GemmProb &P, const CrtTable &T, i
   // residues, four consecutive rows of one column per 32-bit store:
   // accumulator item v of lane l is row 8 (v / 4) + 4 (l / 32) + v % 4, column l % 32
   const double m = T.m[j], inv_m = T.inv_m[j];
+  const int um = T.u[j];
   int8_t *Y = P.Y + j * P.plane_y;
 #pragma unroll
   for (int i = 0; i < FM; ++i)
@@ -191,7 +193,11 @@ __device__ __forceinline__ void mod_tile(const GemmProb &P, const CrtTable &T, i
 #pragma unroll
         for (int t = 0; t < 4; ++t) {
           const double a = (double)acc[i][jj][4 * g + t];
-          const int y = (int)fma(-rint(a * inv_m), m, a);
+          int y = (int)fma(-rint(a * inv_m), m, a);
+          if (P.u_out) {  // |y u| < 2^15: exact
+            const double yu = (double)(y * um);
+            y = (int)fma(-rint(yu * inv_m), m, yu);
+          }
           w |= (uint32_t)(y & 255) << (8 * t);
         }
         if (row < P.M && n < P.N) *reinterpret_cast<uint32_t *>(Y + ((int64_t)(row >> 2) * P.N + n) * 4) = w;

@@ -176,8 +176,6 @@ def test_crt_unsupported_combinations(acse, ctx):
     import torch
     p = PROBLEMS["r6"]()
     args = (p["h"], p["V"], p["gamma"], p["d2aa"], p["d2ab"], p["N"] // 2)
-    with pytest.raises(acse.AcseError, match="UNSUPPORTED"):
-        ctx.residual(*args, precision="int8crt", sigma=True)
     Rb = gen.cotangent(np.random.default_rng(1), 6)
     with pytest.raises(acse.AcseError, match="UNSUPPORTED"):
         ctx.residual_vjp(*args, *Rb, precision="int8crt")

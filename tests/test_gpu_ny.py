@@ -20,7 +20,8 @@ test_oracle_ny.py).
   NY residual equals the closed form of the Valdemoro one.
 * FP32 and split-BF16 block products (the combination FP64) at the bars of
   the Valdemoro mixed modes, 1e-5 and 5e-5 of the largest element, on the
-  residual and on the step's update.
+  residual and on the step's update; the int8 exact-accumulation products at
+  the FP64 bar (residual, share, step; r = 50 stored values).
 * The batched residual with the NY 3-RDM (instances of r = 6, 9, 13 in one
   call) against the oracle per instance.
 * Rejected combinations: the adjoint, the quadratic control, an explicit
@@ -312,10 +313,43 @@ def test_ny_mixed_precision(acse, precision, tol):
         ctx.close()
 
 
+@pytest.mark.parametrize("r,N,seed,pattern", [CASES[1], CASES[3], CASES[5]])
+def test_ny_int8crt_residual_and_step(acse, r, N, seed, pattern):
+    """The int8 exact-accumulation products in the NY share (and the
+    Valdemoro part) at the FP64 bar: residual and share against the oracle,
+    one step's R, U, new 2-RDM and energy."""
+    p = correlated(r, N, seed)
+    sig = sigma_of(p, pattern)
+    print(f"[ny int8crt] r={r} N={N} sigma={pattern}", flush=True)
+    oaa, oab, on2 = ost.residual(p["h"], p["V"], N, p["gamma"], p["d2aa"], p["d2ab"], sigma=sig)
+    vaa, vab, _ = ost.residual(p["h"], p["V"], N, p["gamma"], p["d2aa"], p["d2ab"])
+    o = ost.step(p["h"], p["V"], N, p["gamma"], p["d2aa"], p["d2ab"], 1e-3, sigma=sig)
+    ctx = acse.Context(r_max=r)
+    try:
+        arg = True if pattern == "prefix" else [int(x) for x in sig]
+        args = (p["h"], p["V"], p["gamma"], p["d2aa"], p["d2ab"], N // 2)
+        Raa, Rab, n2 = ctx.residual(*args, precision="int8crt", sigma=arg)
+        Vaa, Vab, _ = ctx.residual(*args, precision="int8crt")
+        Raa, Rab, Vaa, Vab = (x.cpu().numpy() for x in (Raa, Rab, Vaa, Vab))
+        g = ctx.step(*args, eps=1e-3, return_ru=True, precision="int8crt", sigma=arg)
+        for key in ("R_aa", "R_ab", "U_aa", "U_ab", "d2aa", "d2ab"):
+            x = g[key].cpu().numpy()
+            assert np.abs(x - o[key]).max() <= 1e-10 * np.abs(o[key]).max(), key
+        assert abs(g["energy"] - o["energy"]) <= 1e-12 * abs(o["energy"])
+    finally:
+        ctx.close()
+    scale = max(np.abs(oaa).max(), np.abs(oab).max())
+    assert np.abs(Raa - oaa).max() <= 1e-10 * scale and np.abs(Rab - oab).max() <= 1e-10 * scale
+    assert abs(n2 - on2) <= 1e-10 * on2
+    share = max(np.abs(oaa - vaa).max(), np.abs(oab - vab).max())
+    assert np.abs((Raa - Vaa) - (oaa - vaa)).max() <= 1e-9 * share
+    assert np.abs((Rab - Vab) - (oab - vab)).max() <= 1e-9 * share
+
+
 GOLDEN_NY = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "r50_ny_residual.json")
 
 
-@pytest.mark.parametrize("precision,tol", [("fp64", 1e-10), ("fp32", 1e-5), ("bf16x3", 5e-5)])
+@pytest.mark.parametrize("precision,tol", [("fp64", 1e-10), ("fp32", 1e-5), ("bf16x3", 5e-5), ("int8crt", 1e-10)])
 def test_ny_r50_residual_vs_stored_oracle(acse, precision, tol):
     g = json.load(open(GOLDEN_NY))
     p = gen.named(g["workload"])
