@@ -304,9 +304,12 @@ SPIN_GOLDEN = os.path.join(ROOT, "tests", "golden", "r50_spin_step.json")
 
 
 def spin_map_flops(r):
-    """Algorithmic flops of the block products of one spin-block map: 17
-    products of r^2 x r^2 x r^2 (the Y, W H and E terms over spin blocks)."""
-    return 17 * 2.0 * r ** 6
+    """Algorithmic flops of the block products of one spin-block map: 13
+    products of r^2 x r^2 x r^2 (the mixed-spin Y and W H terms and the ten E
+    terms) and the four same-spin Y and W H products with rows and summed pair
+    packed to the pairs i < j, r < s (r(r-1)/2 x r^2 x r(r-1)/2)."""
+    lt = r * (r - 1) // 2
+    return 13 * 2.0 * r ** 6 + 4 * 2.0 * lt * r * r * lt
 
 
 def bench_spin(acse, ctx, gen, torch, steps, warmup, eps, mode="fp64", name="r50s"):

@@ -2493,7 +2493,7 @@ extern "C" acse_status acse_autotune_batched(acse_ctx ctx, int32_t count, const 
 
 namespace {
 
-constexpr int kSpinNat = 48;   // natural r^4 arrays
+constexpr int kSpinNat = 50;   // natural r^4 arrays
 constexpr int kSpinOps = 25;   // GEMM operand buffers
 enum { B0000 = 0, B0101 = 5, B0110 = 6, B1001 = 9, B1010 = 10, B1111 = 15 };
 constexpr int kSix[6] = {B0000, B1111, B0101, B1010, B0110, B1001};
@@ -2505,6 +2505,8 @@ struct SpinWs {
   double *G2p[16] = {}, *Wp[16] = {}, *WPp[16] = {}, *XAp[16] = {}, *Hp[16] = {}, *XtP[16] = {};
   double *f[2] = {}, *t[2] = {}, *part = nullptr, *scal = nullptr;
   double *ops[kSpinOps] = {};  // every GEMM operand buffer, in allocation order
+  // results of the four pair-packed products (rows i < j), row-major [pairs][r^2]
+  double *Pk[4] = {};
   // int8 exact-accumulation products (allocated by the first such call): the
   // residue planes and row exponents of each operand buffer, and the residues
   // of one launch's products
@@ -2540,6 +2542,11 @@ acse_status ensure_spin_ws(acse_ctx c, SpinWs *&out) {
   for (int b : {B0000, B1111, B0101}) { w.Y[b] = take_nat(); w.S[b] = take_nat(); }
   for (int b : {B0000, B1111, B0101, B0110}) w.T[b] = take_nat();
   for (int k = 0; k < 3; ++k) { w.R[k] = take_nat(); w.U[k] = take_nat(); w.Rm[k] = take_nat(); }
+  {  // two packed results (r(r-1)/2 x r^2 doubles each) per natural array
+    double *a = take_nat(), *b = take_nat();
+    const int64_t half = (int64_t)npair_lt(rm) * rm * rm;
+    w.Pk[0] = a; w.Pk[1] = a + half; w.Pk[2] = b; w.Pk[3] = b + half;
+  }
   int nops = 0;
   auto take_op = [&]() {
     double *x = reinterpret_cast<double *>(q);
@@ -2635,33 +2642,68 @@ int spin_op_index(const SpinWs &w, const double *op) {
   return -1;
 }
 
-// FP64 spin operands ([r^2 rows][ld], K = r^2) -> residue planes and row
+// Layout of an operand buffer: the same-spin Y and W H products run with
+// their summed pair (r, s) packed to r < s (K = r(r-1)/2, row stride
+// ld_pair_lt) and their A rows to the pairs i < j; every other operand has
+// r^2 rows over K = r^2.
+struct SpinOpShape {
+  int rows, K;
+  int64_t ld;
+};
+SpinOpShape spin_op_shape(const SpinWs &w, const double *op, int r) {
+  const int r2 = r * r, nlt = npair_lt(r);
+  for (int b : {B0000, B1111}) {
+    if (op == w.G2p[b] || op == w.Wp[b]) return {nlt, nlt, ld_pair_lt(r)};
+    if (op == w.XAp[b] || op == w.Hp[b]) return {r2, nlt, ld_pair_lt(r)};
+  }
+  return {r2, r2, op_ld(r)};
+}
+
+// FP64 spin operands (layouts of spin_op_shape) -> residue planes and row
 // exponents; premul for the operands built from the 2-RDM (one per product).
 acse_status spin_residues(acse_ctx c, SpinWs &w, int r, const std::vector<const double *> &ops, bool premul) {
-  const int r2 = r * r;
   for (size_t first = 0; first < ops.size(); first += kMaxResidueJobs) {
     ResidueBatch b{};
     int rows = 0;
     for (size_t q = first; q < ops.size() && b.count < kMaxResidueJobs; ++q) {
       const int k = spin_op_index(w, ops[q]);
       if (k < 0) return fail(c, ACSE_ERR_HIP, "internal: unknown spin operand buffer");
+      const SpinOpShape sh = spin_op_shape(w, ops[q], r);
       ResidueJob &J = b.job[b.count++];
       J.src = ops[q];
       J.dst = w.cres[k];
       J.e = w.cexp[k];
-      J.plane = op_rows(r) * crt_ldr(r2);
+      J.plane = op_rows(r) * crt_ldr(sh.K);
       J.row_begin = rows;
-      J.K = r2;
-      J.ld = (int)op_ld(r);
-      J.ldr = (int)crt_ldr(r2);
-      J.kbits = crt_kbits(c->crt, r2);
+      J.K = sh.K;
+      J.ld = (int)sh.ld;
+      J.ldr = (int)crt_ldr(sh.K);
+      J.kbits = crt_kbits(c->crt, sh.K);
       J.premul = premul ? 1 : 0;
-      rows += r2;
+      rows += sh.rows;
     }
     b.total_rows = rows;
     HIP_TRY(c, launch_to_residues(b, c->crt, c->stream));
   }
   return ACSE_OK;
+}
+
+// Pair-packed operand from a natural block antisymmetric in its last pair (r,s):
+// rows the pairs i < j (rows_mode 1) or all (k,l) (rows_mode 0), K the pairs
+// r < s, row stride ld_pair_lt, K padding zero.
+hipError_t launch_spin_pack_lt(int r, const double *in, double coef, int rows_mode, double *out, hipStream_t s) {
+  PairPackArgs a{};
+  const int64_t r2 = (int64_t)r * r;
+  a.r = r;
+  a.rows_mode = rows_mode;
+  a.k_le = 0;
+  a.ld = ld_pair_lt(r);
+  a.nterms = 1;
+  a.src[0] = in;
+  a.st[0][0] = r2 * r; a.st[0][1] = r2; a.st[0][2] = r; a.st[0][3] = 1;
+  a.c[0] = coef;
+  a.offdiag[0] = 0;
+  return launch_pack_pairs(GEMM_F64, a, OperandRef{out, nullptr}, s);
 }
 
 // W (natural, six blocks) and the RDM-side GEMM operands of a step.
@@ -2700,10 +2742,15 @@ acse_status spin_prep(acse_ctx c, SpinWs &w, const acse_problem_spin *p) {
     T.t[0] = term4(in, coef, r, f0, f1, f2, f3);
     return launch_pack_op4(r, T, out, ld, s);
   };
-  HIP_TRY(c, pack1(w.G2p[B0000], p->d2aa, 2.0, 0, 1, 2, 3));
-  HIP_TRY(c, pack1(w.G2p[B1111], p->d2bb, 2.0, 0, 1, 2, 3));
+  // same-spin Gamma2 and W: rows i < j, K r < s
+  auto packlt = [&](double *out, const double *in, double coef) {
+    return launch_spin_pack_lt(r, in, coef, 1, out, s);
+  };
+  HIP_TRY(c, packlt(w.G2p[B0000], p->d2aa, 2.0));
+  HIP_TRY(c, packlt(w.G2p[B1111], p->d2bb, 2.0));
   HIP_TRY(c, pack1(w.G2p[B0101], p->d2ab, 2.0, 0, 1, 2, 3));
-  for (int b : {B0000, B1111, B0101}) HIP_TRY(c, pack1(w.Wp[b], w.W[b], 1.0, 0, 1, 2, 3));
+  for (int b : {B0000, B1111}) HIP_TRY(c, packlt(w.Wp[b], w.W[b], 1.0));
+  HIP_TRY(c, pack1(w.Wp[B0101], w.W[B0101], 1.0, 0, 1, 2, 3));
   for (int b : kSix) HIP_TRY(c, pack1(w.WPp[b], w.W[b], 1.0, 0, 3, 1, 2));
   if (c->crt_moduli) {
     acse_status st = ensure_spin_crt(c, w);
@@ -2801,8 +2848,13 @@ acse_status spin_map(acse_ctx c, SpinWs &w, int r, const double *ga, const doubl
       T.t[0] = term4(in, 1.0, r, f0, f1, f2, f3);
       return launch_pack_op4(r, T, out, ld, s);
     };
-    for (int b : {B0000, B1111, B0101}) HIP_TRY(c, pack1(w.XAp[b], w.XA[b], 0, 1, 2, 3));
-    for (int b : {B0000, B1111, B0101, B1001}) HIP_TRY(c, pack1(w.Hp[b], w.H[b], 0, 1, 2, 3));
+    // same-spin X_A and H: rows (k,l), K r < s (both antisymmetric in (r,s))
+    for (int b : {B0000, B1111}) {
+      HIP_TRY(c, launch_spin_pack_lt(r, w.XA[b], 1.0, 0, w.XAp[b], s));
+      HIP_TRY(c, launch_spin_pack_lt(r, w.H[b], 1.0, 0, w.Hp[b], s));
+    }
+    HIP_TRY(c, pack1(w.XAp[B0101], w.XA[B0101], 0, 1, 2, 3));
+    for (int b : {B0101, B1001}) HIP_TRY(c, pack1(w.Hp[b], w.H[b], 0, 1, 2, 3));
     for (int b : kSix) HIP_TRY(c, pack1(w.XtP[b], w.Xt[b], 0, 2, 1, 3));  // rows (k,i), K (p,s)
     if (c->crt_moduli) {
       std::vector<const double *> ops;
@@ -2815,7 +2867,9 @@ acse_status spin_map(acse_ctx c, SpinWs &w, int r, const double *ga, const doubl
   }
   // the 17 products in three launches of 6, 6 and 5; the second E term of the
   // four blocks that have one accumulates in the last launch, after the
-  // launch that wrote the first
+  // launch that wrote the first.  The same-spin Y and W H products run over
+  // the pairs i < j and r < s (a quarter of the flops; alpha doubled for the
+  // summed pair) into row-major scratch, unpacked afterwards.
   {
     const int kp = gemm_kp(GEMM_F64, (int)r2, ld);
     auto prob = [&](GemmProb &P, const double *A, const double *B, double alpha, double *C, bool ph, int acc) {
@@ -2825,6 +2879,15 @@ acse_status spin_map(acse_ctx c, SpinWs &w, int r, const double *ga, const doubl
       if (ph) { P.sm1 = r; P.sm0 = r3; P.sn1 = r2; P.sn0 = 1; }      // rows (k,i), cols (j,l) -> [i,j,k,l]
       else { P.sm1 = r3; P.sm0 = r2; P.sn1 = r; P.sn0 = 1; }         // natural [(ij)][(kl)]
       P.ksplit = 1; P.kchunk = kp; P.accumulate = acc;
+    };
+    const int nlt = npair_lt(r);
+    const int64_t ldlt = ld_pair_lt(r);
+    auto probp = [&](GemmProb &P, const double *A, const double *B, double alpha, double *C) {
+      P = GemmProb{};
+      P.A = A; P.B = B; P.C = C; P.alpha = alpha;
+      P.M = nlt; P.N = (int)r2; P.Kp = gemm_kp(GEMM_F64, nlt, (int)ldlt); P.ld = (int)ldlt; P.rdiv = 1;
+      P.sm1 = r2; P.sm0 = 0; P.sn1 = 1; P.sn0 = 0;                   // row-major [pairs][r^2]
+      P.ksplit = 1; P.kchunk = P.Kp; P.accumulate = 0;
     };
     const int cfg = map_cfg(c, GEMM_F64, r, -1);
     // FP64 products, or the int8 exact-accumulation ones from the residues of
@@ -2836,21 +2899,21 @@ acse_status spin_map(acse_ctx c, SpinWs &w, int r, const double *ga, const doubl
         HIP_TRY(c, gemm_launch(GEMM_F64, cfg, b, s));
         return ACSE_OK;
       }
-      const int r2i = (int)r2;
-      const int64_t plane = op_rows(r) * crt_ldr(r2i);
       int64_t yoff = 0;
       for (int q = 0; q < b.count; ++q) {
         GemmProb &P = b.p[q];
         const int ka = spin_op_index(w, static_cast<const double *>(P.A));
         const int kb = spin_op_index(w, static_cast<const double *>(P.B));
         if (ka < 0 || kb < 0) return fail(c, ACSE_ERR_HIP, "internal: unknown spin operand buffer");
+        const int K = spin_op_shape(w, static_cast<const double *>(P.A), r).K;
         P.A = w.cres[ka];
         P.B = w.cres[kb];
-        P.ld = P.Kp = (int)crt_ldr(r2i);
-        P.plane_a = P.plane_b = plane;
+        P.ld = P.Kp = (int)crt_ldr(K);
+        P.kchunk = P.Kp;
+        P.plane_a = P.plane_b = op_rows(r) * crt_ldr(K);
         P.ea = w.cexp[ka];
         P.eb = w.cexp[kb];
-        P.kshift = 2 * crt_kbits(c->crt, r2i);
+        P.kshift = 2 * crt_kbits(c->crt, K);
         P.Y = w.cy + yoff;
         P.plane_y = crt_residue_out_bytes(P.M, P.N);
         yoff += (int64_t)c->crt.nmod * P.plane_y;
@@ -2866,13 +2929,18 @@ acse_status spin_map(acse_ctx c, SpinWs &w, int r, const double *ga, const doubl
     acse_status st;
     GemmBatch b1{};
     b1.count = 6;
-    prob(b1.p[0], w.G2p[B0000], w.XAp[B0000], 1.0, w.Y[B0000], false, 0);
-    prob(b1.p[1], w.G2p[B1111], w.XAp[B1111], 1.0, w.Y[B1111], false, 0);
+    probp(b1.p[0], w.G2p[B0000], w.XAp[B0000], 2.0, w.Pk[0]);
+    probp(b1.p[1], w.G2p[B1111], w.XAp[B1111], 2.0, w.Pk[1]);
     prob(b1.p[2], w.G2p[B0101], w.XAp[B0101], 2.0, w.Y[B0101], false, 0);
-    prob(b1.p[3], w.Wp[B0000], w.Hp[B0000], 1.0, w.T[B0000], false, 0);
-    prob(b1.p[4], w.Wp[B1111], w.Hp[B1111], 1.0, w.T[B1111], false, 0);
+    probp(b1.p[3], w.Wp[B0000], w.Hp[B0000], 2.0, w.Pk[2]);
+    probp(b1.p[4], w.Wp[B1111], w.Hp[B1111], 2.0, w.Pk[3]);
     prob(b1.p[5], w.Wp[B0101], w.Hp[B0101], 2.0, w.T[B0101], false, 0);
     if ((st = launch(b1)) != ACSE_OK) return st;
+    {
+      StageTimer t4(c, 4);
+      double *const dst[4] = {w.Y[B0000], w.Y[B1111], w.T[B0000], w.T[B1111]};
+      for (int k = 0; k < 4; ++k) HIP_TRY(c, launch_unpack_rows_lt(r, w.Pk[k], r2, dst[k], s));
+    }
     // E^{ij}_{kl} = 2 sum Xt^{kp}_{is} W^{jp}_{sl}: the first terms of the four
     // blocks with two, then the rest
     GemmBatch b2{};

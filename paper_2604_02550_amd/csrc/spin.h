@@ -44,6 +44,10 @@ hipError_t launch_pair_traces(int r, int count, const double *const *in, double 
 // the traces).
 hipError_t launch_spin_update(int r, double eps, double *const *d2, const double *const *U, const double *traces,
                               hipStream_t s);
+// Natural r^4 array from a product whose rows ran over the pairs i < j of an
+// antisymmetric pair (row-major, row stride ldc, columns (k,l) all r^2):
+// out[i,j,k,l] = sign(i,j) C[pair(min,max)][k r + l], zero for i = j.
+hipError_t launch_unpack_rows_lt(int r, const double *C, int64_t ldc, double *out, hipStream_t s);
 // 1-RDM per spin from the new 2-RDM blocks: ga = c (Tr_2 d2aa + Tr_2 d2ab),
 // gb = c (Tr_2 d2bb + Tr_1 d2ab), c = 2 / (N - 1).
 hipError_t launch_spin_1rdm(int r, int N, const double *d2aa, const double *d2bb, const double *d2ab, double *ga,

@@ -125,6 +125,22 @@ __global__ void k_spin_1rdm(int r, double c, const double *__restrict__ aa, cons
   gb[e] = c * vb;
 }
 
+// out[i,j,k,l] = sign(i,j) C[pair(min(i,j), max(i,j))][k r + l], zero for i = j.
+__global__ void __launch_bounds__(256)
+k_unpack_rows_lt(int r, const double *__restrict__ C, int64_t ldc, double *__restrict__ out) {
+  const int64_t r2 = (int64_t)r * r;
+  const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (e >= r2 * r2) return;
+  const int64_t row = e / r2, col = e - row * r2;
+  const int i = (int)(row / r), j = (int)(row - (int64_t)i * r);
+  double v = 0.0;
+  if (i != j) {
+    v = C[(int64_t)pair_lt(r, min(i, j), max(i, j)) * ldc + col];
+    if (i > j) v = -v;
+  }
+  out[e] = v;
+}
+
 inline dim3 grid1(int64_t n) { return dim3((unsigned)((n + 255) / 256)); }
 
 }  // namespace
@@ -166,6 +182,11 @@ hipError_t launch_spin_update(int r, double eps, double *const *d2, const double
   for (int q = 0; q < 3; ++q) { a.d2[q] = d2[q]; a.U[q] = U[q]; }
   const int64_t n = (int64_t)r * r * r * r;
   hipLaunchKernelGGL(k_spin_update, dim3((unsigned)((n + 255) / 256), 3), dim3(256), 0, s, r, eps, a, traces);
+  return hipGetLastError();
+}
+
+hipError_t launch_unpack_rows_lt(int r, const double *C, int64_t ldc, double *out, hipStream_t s) {
+  hipLaunchKernelGGL(k_unpack_rows_lt, grid1((int64_t)r * r * r * r), dim3(256), 0, s, r, C, ldc, out);
   return hipGetLastError();
 }
 
