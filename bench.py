@@ -58,7 +58,7 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--vjp-modes", default="fp64,fp32",
                     help="precisions of the adjoint (VJP) measurement ('' to skip)")
-    ap.add_argument("--batched-modes", default="fp64,fp32",
+    ap.add_argument("--batched-modes", default="int8crt,fp64,fp32",
                     help="precisions of the batched-instances measurement ('' to skip)")
     ap.add_argument("--solve-controls", default="fixed,backtrack,quadratic",
                     help="step controls of acse_solve timed on the workload (FP64); empty to skip")
@@ -112,7 +112,8 @@ def bench_batched(acse, ctx, gen, torch, modes, steps, warmup):
         opts = acse.Context.options(mode)
         popts = acse.Context.options(mode, flags=acse.FLAG_BATCH_PERSISTENT)
         ctx.autotune_batched_raw(probs, opts)          # every r, as single calls take them
-        best, tile_ms = ctx.autotune_batched_raw(probs, popts)
+        if mode != "int8crt":
+            best, tile_ms = ctx.autotune_batched_raw(probs, popts)
 
         def timed(fn):
             for _ in range(warmup):
@@ -138,8 +139,15 @@ def bench_batched(acse, ctx, gen, torch, modes, steps, warmup):
                 ctx.residual_raw(prob, opts, o[0], o[1], want_norm=False)
 
         ms_b = timed(batched)
-        ms_p = timed(persistent)
         ms_s = timed(sequential)
+        if mode == "int8crt":   # the persistent strategy runs the floating-point products only
+            res[mode] = dict(instances=len(batch), sizes=sorted({p["r"] for p in batch}),
+                             batched_ms=ms_b, sequential_ms=ms_s,
+                             batched_evals_per_s=len(batch) * 1e3 / ms_b,
+                             sequential_evals_per_s=len(batch) * 1e3 / ms_s,
+                             speedup=ms_s / ms_b, useful_tflops=flops / (ms_b * 1e-3) / 1e12)
+            continue
+        ms_p = timed(persistent)
         ctx.profile(True)
         persistent()
         prof = ctx.profile_read()

@@ -94,9 +94,11 @@ typedef enum {
                       only rounding is that of the operands to k bits relative to their
                       row's largest magnitude.  Residual, update map, step, autotune
                       and the Euler iteration (fixed and backtracking controls), with
-                      the Valdemoro or the NY reconstruction, and the spin-block calls;
-                      the adjoint, the quadratic control, the batched residual and
-                      acse_residual_noalloc are ACSE_ERR_UNSUPPORTED with it.  The first
+                      the Valdemoro or the NY reconstruction, the spin-block calls and
+                      the batched residual on its lanes (one residue workspace per lane,
+                      allocated by the first such batch); the adjoint, the quadratic
+                      control, the persistent batch and acse_residual_noalloc are
+                      ACSE_ERR_UNSUPPORTED with it.  The first
                       call allocates residue buffers for r_max: 12 x (15 x op_rows x
                       round_up(r_max^2, 256) + 4 op_rows) bytes for the operands
                       (op_rows = r_max^2 rounded up to 256) and 15 x about 4.5 r_max^4

@@ -47,6 +47,15 @@ constexpr int kProbsPerMap = 6;  // pair-index products of one residual map
 constexpr int kTuneReps = 5;     // timed repetitions per tile configuration in the autotuners
 constexpr int kAbPackMinR = 40;  // smallest r whose alpha-beta pp adjoint products run packed
 
+// Residue planes and row exponents of the 12 operand buffers and the residues
+// of the six products, for the int8 exact-accumulation products.
+struct CrtWs {
+  void *base = nullptr;
+  int8_t *cres[12] = {};
+  int *cexp[12] = {};
+  int8_t *cy = nullptr;
+};
+
 struct Workspace {
   // natural FP64 r^4 arrays
   double *Aaa, *Aab, *Waa, *Wab, *Haa, *Hab, *G2aa, *G2ab, *T1, *Caa, *Cab;
@@ -56,6 +65,7 @@ struct Workspace {
   char *op[12];
   // small arrays
   double *fpart, *f, *tpart, *t, *partial, *scal;
+  CrtWs *crt;  // residue buffers used with this workspace (int8 products)
 };
 
 }  // namespace
@@ -116,15 +126,12 @@ struct acse_ctx_s {
   // set by acse_step around its update map: the 2-RDM has not changed since
   // the residual map, whose cumulant blocks and their operand layouts stand
   bool ny_reuse_d = false;
-  // exact-accumulation int8 products (ACSE_INT8CRT): residue planes and row
-  // exponents of the 12 operand buffers (allocated by the first such call, for
-  // r_max and the largest modulus count) and the table of the call's moduli
-  void *cbase = nullptr;
-  int64_t cbytes = 0;
-  int8_t *cres[12] = {};
-  int *cexp[12] = {};
-  int64_t cres_bytes = 0;  // bytes of one operand's residue buffer
-  int8_t *cy = nullptr;    // residues of the six products (all moduli)
+  // exact-accumulation int8 products (ACSE_INT8CRT): residue buffers of the
+  // context's workspace and of the four batch lanes (each allocated by its
+  // first use, for r_max and the largest modulus count) and the table of the
+  // call's moduli
+  CrtWs cw{};
+  CrtWs lane_cw[4]{};
   CrtTable crt{};
   int crt_moduli = 0;      // modulus count of the call in progress (set by validate)
   // spin-block path for states of any S_z (allocated by its first call, for r_max)
@@ -321,31 +328,37 @@ int64_t crt_out_bytes_per_modulus(int r) {
          crt_residue_out_bytes(npair_le(r), r2);
 }
 
-// Residue workspace of the int8 exact-accumulation products (first use), and
-// the moduli table of the call in progress.
-acse_status ensure_crt(acse_ctx c) {
-  if (!c->cbase) {
-    const int rm = c->r_max;
-    const int64_t rows = op_rows(rm);
-    c->cres_bytes = round_up((int64_t)kMaxModuli * rows * crt_ldr(rm * rm), 256);
-    const int64_t ebytes = round_up(rows * (int64_t)sizeof(int), 256);
-    const int64_t ybytes = round_up(kMaxModuli * crt_out_bytes_per_modulus(rm), 256);
-    const int64_t bytes = kNumOps * (c->cres_bytes + ebytes) + ybytes;
-    if (hipMalloc(&c->cbase, bytes) != hipSuccess) {
-      (void)hipGetLastError();
-      c->cbase = nullptr;
-      return fail(c, ACSE_ERR_NOMEM, "cannot allocate the int8 residue workspace (" + std::to_string(bytes) + " bytes)");
-    }
-    c->cbytes = bytes;
-    char *q = static_cast<char *>(c->cbase);
-    for (int k = 0; k < kNumOps; ++k) {
-      c->cres[k] = reinterpret_cast<int8_t *>(q);
-      q += c->cres_bytes;
-      c->cexp[k] = reinterpret_cast<int *>(q);
-      q += ebytes;
-    }
-    c->cy = reinterpret_cast<int8_t *>(q);
+// Allocates one residue workspace (first use), for r_max.
+acse_status alloc_crt_ws(acse_ctx c, CrtWs &cw) {
+  if (cw.base) return ACSE_OK;
+  const int rm = c->r_max;
+  const int64_t rows = op_rows(rm);
+  const int64_t rbytes = round_up((int64_t)kMaxModuli * rows * crt_ldr(rm * rm), 256);
+  const int64_t ebytes = round_up(rows * (int64_t)sizeof(int), 256);
+  const int64_t ybytes = round_up(kMaxModuli * crt_out_bytes_per_modulus(rm), 256);
+  const int64_t bytes = kNumOps * (rbytes + ebytes) + ybytes;
+  if (hipMalloc(&cw.base, bytes) != hipSuccess) {
+    (void)hipGetLastError();
+    cw.base = nullptr;
+    return fail(c, ACSE_ERR_NOMEM, "cannot allocate the int8 residue workspace (" + std::to_string(bytes) + " bytes)");
   }
+  char *q = static_cast<char *>(cw.base);
+  for (int k = 0; k < kNumOps; ++k) {
+    cw.cres[k] = reinterpret_cast<int8_t *>(q);
+    q += rbytes;
+    cw.cexp[k] = reinterpret_cast<int *>(q);
+    q += ebytes;
+  }
+  cw.cy = reinterpret_cast<int8_t *>(q);
+  return ACSE_OK;
+}
+
+// Residue workspace of the context's workspace (first use), and the moduli
+// table of the call in progress.
+acse_status ensure_crt(acse_ctx c) {
+  acse_status st = alloc_crt_ws(c, c->cw);
+  if (st != ACSE_OK) return st;
+  c->ws.crt = &c->cw;
   if (c->crt.nmod != c->crt_moduli && !crt_table(c->crt_moduli, c->crt))
     return fail(c, ACSE_ERR_ARG, "no moduli table for " + std::to_string(c->crt_moduli) + " moduli");
   return ACSE_OK;
@@ -384,8 +397,8 @@ acse_status crt_residues(acse_ctx c, const Workspace &w, int r, bool rdm_side) {
     const OpShape sh = op_shape(idx, r);
     ResidueJob &J = b.job[q];
     J.src = reinterpret_cast<const double *>(w.op[idx]);
-    J.dst = c->cres[idx];
-    J.e = c->cexp[idx];
+    J.dst = w.crt->cres[idx];
+    J.e = w.crt->cexp[idx];
     J.plane = crt_plane(idx, r);
     J.row_begin = rows;
     J.K = sh.K;
@@ -548,8 +561,7 @@ void map_probs(const Workspace &w, GemmPrec prec, int r, GemmProb *out) {
 }
 
 // The same six products on the residue planes of the int8 exact-accumulation mode.
-void map_probs_crt(acse_ctx c, int r, GemmProb *out) {
-  const Workspace &w = c->ws;
+void map_probs_crt(acse_ctx c, const Workspace &w, int r, GemmProb *out) {
   map_probs(w, GEMM_F64, r, out);  // outputs, shapes, alphas and store maps
   static const int pa[6] = {OP_DAA, OP_DS, OP_DA, OP_LP, OP_LM, OP_L3};
   static const int pb[6] = {OP_BAA, OP_BS, OP_BA, OP_RP, OP_RM, OP_R3};
@@ -557,16 +569,16 @@ void map_probs_crt(acse_ctx c, int r, GemmProb *out) {
   for (int q = 0; q < kProbsPerMap; ++q) {
     GemmProb &P = out[q];
     const int K = op_shape(pa[q], r).K;
-    P.A = c->cres[pa[q]];
-    P.B = c->cres[pb[q]];
+    P.A = w.crt->cres[pa[q]];
+    P.B = w.crt->cres[pb[q]];
     P.A2 = P.B2 = nullptr;
     P.ld = P.Kp = (int)crt_ldr(K);
     P.plane_a = crt_plane(pa[q], r);
     P.plane_b = crt_plane(pb[q], r);
-    P.ea = c->cexp[pa[q]];
-    P.eb = c->cexp[pb[q]];
+    P.ea = w.crt->cexp[pa[q]];
+    P.eb = w.crt->cexp[pb[q]];
     P.kshift = 2 * crt_kbits(c->crt, K);
-    P.Y = c->cy + yoff;
+    P.Y = w.crt->cy + yoff;
     P.plane_y = crt_residue_out_bytes(P.M, P.N);
     yoff += (int64_t)c->crt.nmod * P.plane_y;
   }
@@ -929,7 +941,7 @@ acse_status run_map(acse_ctx c, const acse_problem *p, GemmPrec prec, int cfg, c
   GemmBatch batch{};
   batch.count = kProbsPerMap;
   if (prec == GEMM_I8CRT) {
-    map_probs_crt(c, r, batch.p);
+    map_probs_crt(c, w, r, batch.p);
     {
       StageTimer t3(c, 3);
       HIP_TRY(c, gemm_crt_launch(batch, c->crt, c->stream));
@@ -1079,7 +1091,9 @@ acse_status acse_destroy(acse_ctx ctx) {
   if (ctx->vbase) (void)hipFree(ctx->vbase);
   if (ctx->sbase) (void)hipFree(ctx->sbase);
   if (ctx->nybase) (void)hipFree(ctx->nybase);
-  if (ctx->cbase) (void)hipFree(ctx->cbase);
+  if (ctx->cw.base) (void)hipFree(ctx->cw.base);
+  for (CrtWs &cw : ctx->lane_cw)
+    if (cw.base) (void)hipFree(cw.base);
   if (ctx->spbase) (void)hipFree(ctx->spbase);
   if (ctx->nycbase) (void)hipFree(ctx->nycbase);
   release_spin_ws(ctx);
@@ -2145,9 +2159,9 @@ acse_status validate_batch(acse_ctx c, int32_t count, const acse_problem *probs,
   if (c->ny_on && opts->ny_sigma)
     return fail(c, ACSE_ERR_ARG, "a batch takes each instance's reference occupations from its n_alpha: "
                                  "ny_sigma must be NULL");
-  if (c->crt_moduli)
-    return fail(c, ACSE_ERR_UNSUPPORTED, "the batched residual runs in FP64, FP32 or split BF16, not in int8 "
-                                         "exact accumulation");
+  if (c->crt_moduli && (c->ny_on || (opts && (opts->flags & ACSE_FLAG_BATCH_PERSISTENT))))
+    return fail(c, ACSE_ERR_UNSUPPORTED, "int8 exact accumulation in a batch runs on the lanes (no "
+                                         "ACSE_FLAG_BATCH_PERSISTENT) with the Valdemoro reconstruction");
   return ACSE_OK;
 }
 
@@ -2256,6 +2270,12 @@ acse_status run_lanes(acse_ctx c, int count, const acse_problem *probs, GemmPrec
                       double *const *Raa, double *const *Rab, BatchPlan &plan, const std::vector<int> &order,
                       const std::vector<int> &lane, int ns) {
   acse_status st;
+  if (prec == GEMM_I8CRT) {
+    // one residue workspace per lane: the instances of a lane run in order
+    for (int q = 0; q < ns; ++q)
+      if ((st = alloc_crt_ws(c, c->lane_cw[q])) != ACSE_OK) return st;
+    for (int i = 0; i < count; ++i) plan.ws[i].crt = &c->lane_cw[lane[i]];
+  }
   if ((st = fork_sides(c, ns)) != ACSE_OK) return st;
   const ActiveBits none{};
   auto one = [&](int i) -> acse_status {
@@ -2271,8 +2291,16 @@ acse_status run_lanes(acse_ctx c, int count, const acse_problem *probs, GemmPrec
     if ((s2 = map_front(c, p, prec, w.Aaa, w.Aab, w)) != ACSE_OK) return s2;
     GemmBatch b{};
     b.count = kProbsPerMap;
-    map_probs(w, prec, p->r, b.p);
-    {
+    if (prec == GEMM_I8CRT) {
+      map_probs_crt(c, w, p->r, b.p);
+      {
+        StageTimer t3(c, 3);
+        HIP_TRY(c, gemm_crt_launch(b, c->crt, c->stream));
+      }
+      StageTimer t4(c, 4);
+      HIP_TRY(c, crt_combine_launch(b, c->crt, c->stream));
+    } else {
+      map_probs(w, prec, p->r, b.p);
       StageTimer t3(c, 3);
       HIP_TRY(c, gemm_launch(prec, instance_cfg(c, prec, p->r, tile), b, c->stream));
     }
@@ -2379,6 +2407,7 @@ extern "C" acse_status acse_residual_batched(acse_ctx ctx, int32_t count, const 
     if ((st = check_out(ctx, R_ab[i], "R_ab[i]")) != ACSE_OK) return st;
   }
   HIP_TRY(ctx, hipSetDevice(ctx->device));
+  if (ctx->crt_moduli && (st = ensure_crt(ctx)) != ACSE_OK) return st;
   const GemmPrec prec = prec_of(opts);
   BatchPlan plan;
   if ((st = ensure_batch(ctx, count, probs, plan)) != ACSE_OK) return st;

@@ -153,3 +153,19 @@ def test_batched_errors(acse, ctx):
     bad_prob = acse.Problem(prob.r, 1, 2, prob.h, prob.V, prob.d1, prob.d2aa, prob.d2ab)
     with pytest.raises(acse.AcseError, match="instance 1"):
         ctx.residual_batched_raw([prob, bad_prob], ctx.options("fp64"), [out[0]] * 2, [out[1]] * 2)
+
+
+def test_int8crt_batch_on_lanes(ctx, big_batch):
+    """The int8 exact-accumulation products in a batch (lanes, one residue
+    workspace per lane): the small mixed batch against the oracle at the FP64
+    bar, and every instance of the 12-instance workload bitwise equal to its
+    own single int8crt call."""
+    import torch
+    small = small_batch()
+    print("[batched int8crt] small batch", flush=True)
+    for p, (Raa, Rab, n2) in zip(small, ctx.residual_batched(small, "int8crt")):
+        check_oracle(p, Raa, Rab, n2, TOL64)
+    res = ctx.residual_batched(big_batch, "int8crt")
+    for i, (p, (Raa, Rab, n2)) in enumerate(zip(big_batch, res)):
+        Saa, Sab, s2 = ctx.residual(p["h"], p["V"], p["gamma"], p["d2aa"], p["d2ab"], p["N"] // 2, "int8crt")
+        assert torch.equal(Raa, Saa) and torch.equal(Rab, Sab) and n2 == s2, i

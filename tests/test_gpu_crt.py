@@ -181,7 +181,7 @@ def test_crt_unsupported_combinations(acse, ctx):
         ctx.residual_vjp(*args, *Rb, precision="int8crt")
     inst = [dict(h=p["h"], V=p["V"], N=p["N"], gamma=p["gamma"], d2aa=p["d2aa"], d2ab=p["d2ab"])]
     with pytest.raises(acse.AcseError, match="UNSUPPORTED"):
-        ctx.residual_batched(inst, precision="int8crt")
+        ctx.residual_batched(inst, precision="int8crt", flags=acse.FLAG_BATCH_PERSISTENT)
     with pytest.raises(acse.AcseError, match="UNSUPPORTED"):
         ctx.solve(*args, control="quadratic", precision="int8crt", max_iter=1)
     with pytest.raises(acse.AcseError, match="UNSUPPORTED"):
