@@ -40,7 +40,7 @@ import numpy as np
 
 from . import adjoint, rdm
 from .residual import residual_map
-from .step import active_mask, restore_traces
+from .step import active_mask, restore_block_traces, restore_traces
 
 FIXED, BACKTRACK, QUADRATIC = 0, 1, 2
 STOP_MAX_ITER, STOP_CONVERGED, STOP_ENERGY_ROSE, STOP_NORM_ROSE = 0, 1, 2, 3
@@ -172,4 +172,77 @@ def euler(h, V, N, gamma, d2aa, d2ab, eps=1e-3, de_tol=1e-6, max_iter=100, contr
             out["stop"] = STOP_CONVERGED
             break
     out.update(gamma=gamma, d2aa=d2aa, d2ab=d2ab, energy=E, norm2=f)
+    return out
+
+
+def euler_spin(h, V, Na, Nb, ga, gb, d2aa, d2bb, d2ab, eps=1e-3, de_tol=1e-6, max_iter=100, control=FIXED,
+               max_halvings=8, active=None):
+    """The iteration of ``euler`` for a state of any S_z, on its three 2-RDM
+    spin blocks (alpha-alpha, beta-beta, alpha-beta) and one 1-RDM per spin:
+    the same stopping rules and the FIXED and BACKTRACK controls; each block is
+    rescaled to its own trace before the step (a block of trace zero is set to
+    zero) and both 1-RDMs are contracted from the new 2-RDM.  Returns a dict
+    with ga, gb, d2aa, d2bb, d2ab of the returned state and the fields of
+    ``euler``."""
+    if control not in (FIXED, BACKTRACK):
+        raise ValueError("the spin-block iteration takes the FIXED or BACKTRACK control")
+    h = np.asarray(h, dtype=np.float64)
+    V = np.asarray(V, dtype=np.float64)
+    r = h.shape[0]
+    N = Na + Nb
+    K = rdm.reduced_hamiltonian(h, V, N)
+    mask = active_mask(active, r)
+    blocks = tuple(np.array(x, dtype=np.float64) for x in (d2aa, d2bb, d2ab))
+    ga = np.array(ga, dtype=np.float64)
+    gb = np.array(gb, dtype=np.float64)
+    z = np.zeros((r, r))
+
+    def residual(ga, gb, blocks):
+        d1, d2 = rdm.spin_blocks_to_spin_orbital(ga, gb, *blocks)
+        R = residual_map(K, d1, d2, hermitian=True).numpy()
+        return R, float(np.sum(R ** 2)), d1, d2, float(np.sum(K * d2))
+
+    R, f, d1, d2, E = residual(ga, gb, blocks)
+    out = dict(energy0=E, norm2_0=f, trials=[], iterations=0, stop=STOP_MAX_ITER, eps_last=0.0)
+    e = eps
+    for n in range(max_iter):
+        Rm = R if mask is None else R * mask
+        U = residual_map(Rm, d1, d2, hermitian=False).numpy()
+        ublocks = rdm.spin_orbital_to_spin_blocks(U)
+        traces = tuple(float(np.einsum('pqpq->', b)) for b in blocks)
+
+        def run(x):
+            new, _ = restore_block_traces(tuple(b + x * u for b, u in zip(blocks, ublocks)), traces)
+            _, d2n = rdm.spin_blocks_to_spin_orbital(z, z, *new)
+            g1 = rdm.contract_to_1rdm(d2n, N)
+            g1a, g1b = g1[:r, :r].copy(), g1[r:, r:].copy()
+            Rt, ft, d1t, d2t, Et = residual(g1a, g1b, new)
+            return dict(eps=x, blocks=new, ga=g1a, gb=g1b, E=Et, f=ft, R=Rt, d1=d1t, d2=d2t)
+
+        trials = [run(e)]
+        chosen = trials[0] if (trials[0]["E"] <= E and trials[0]["f"] <= f) else None
+        cand = e
+        halvings = 0
+        while chosen is None and control == BACKTRACK and halvings < max_halvings:
+            cand = 0.5 * cand
+            halvings += 1
+            t = run(cand)
+            trials.append(t)
+            if t["E"] <= E and t["f"] <= f:
+                chosen = t
+        for q in trials:
+            out["trials"].append((q["eps"], q["E"], q["f"], n, q is chosen))
+        if chosen is None:
+            out["stop"] = STOP_ENERGY_ROSE if trials[-1]["E"] > E else STOP_NORM_ROSE
+            break
+        dE = chosen["E"] - E
+        blocks, ga, gb = chosen["blocks"], chosen["ga"], chosen["gb"]
+        E, f, R, d1, d2 = chosen["E"], chosen["f"], chosen["R"], chosen["d1"], chosen["d2"]
+        e = chosen["eps"]
+        out["iterations"] = n + 1
+        out["eps_last"] = e
+        if abs(dE) < de_tol:
+            out["stop"] = STOP_CONVERGED
+            break
+    out.update(ga=ga, gb=gb, d2aa=blocks[0], d2bb=blocks[1], d2ab=blocks[2], energy=E, norm2=f)
     return out

@@ -161,3 +161,46 @@ def test_quadratic_control_lowers_the_norm_faster(r6):
     assert quad["energy"] < fixed["energy"]
     accepted = [t for t in quad["trials"] if t[4]]
     assert np.all(np.diff([quad["norm2_0"]] + [t[2] for t in accepted]) <= 0)
+
+
+def test_euler_spin_on_singlet_inputs_is_the_singlet_iteration():
+    """The spin-block iteration on a singlet given as three blocks (beta =
+    alpha, pair-exchange symmetric alpha-beta) takes the singlet iteration's
+    trials, decisions and final state; with backtracking from a step size that
+    raises ||R|| the halvings agree too."""
+    from oracle import solve as sv
+    p = gen.problem(5, 4, 10, seed=3)
+    args = (p["h"], p["V"], p["N"], p["gamma"], p["d2aa"], p["d2ab"])
+    for eps, ctrl in ((1e-3, sv.FIXED), (0.2, sv.BACKTRACK)):
+        s = sv.euler(*args, eps=eps, de_tol=0.0, max_iter=3, control=ctrl, max_halvings=4)
+        g = sv.euler_spin(p["h"], p["V"], 2, 2, p["gamma"], p["gamma"], p["d2aa"], p["d2aa"], p["d2ab"],
+                          eps=eps, de_tol=0.0, max_iter=3, control=ctrl, max_halvings=4)
+        assert g["stop"] == s["stop"] and g["iterations"] == s["iterations"]
+        assert len(g["trials"]) == len(s["trials"])
+        for a, b in zip(g["trials"], s["trials"]):
+            assert a[0] == b[0] and a[3:] == b[3:]
+            assert abs(a[1] - b[1]) < 1e-11 * abs(b[1]) and abs(a[2] - b[2]) < 1e-11 * b[2]
+        for k, ref in (("d2aa", s["d2aa"]), ("d2bb", s["d2aa"]), ("d2ab", s["d2ab"]), ("ga", s["gamma"])):
+            assert np.abs(g[k] - ref).max() < 1e-12 * max(1.0, np.abs(ref).max()), k
+
+
+def test_euler_spin_steps_are_step_spin_steps():
+    """Every accepted fixed-eps step of the spin-block iteration is one
+    step_spin of the state before it (energy and blocks)."""
+    from oracle import rdm
+    from oracle import solve as sv
+    from oracle import step as st
+    p = gen.spin_problem(5, 3, 1, 10, seed=2)
+    z = np.zeros((5, 5))
+    _, d2 = rdm.spin_blocks_to_spin_orbital(z, z, p["d2aa"], p["d2bb"], p["d2ab"])
+    g = rdm.contract_to_1rdm(d2, 4)
+    ga, gb = g[:5, :5].copy(), g[5:, 5:].copy()
+    o = sv.euler_spin(p["h"], p["V"], 3, 1, ga, gb, p["d2aa"], p["d2bb"], p["d2ab"], eps=1e-2, de_tol=0.0,
+                      max_iter=2)
+    s1 = st.step_spin(p["h"], p["V"], 3, 1, ga, gb, p["d2aa"], p["d2bb"], p["d2ab"], 1e-2)
+    s2 = st.step_spin(p["h"], p["V"], 3, 1, s1["gamma_a"], s1["gamma_b"], s1["d2aa"], s1["d2bb"], s1["d2ab"], 1e-2)
+    assert o["iterations"] == 2 and [t[4] for t in o["trials"]] == [True, True]
+    assert abs(o["trials"][0][1] - s1["energy"]) < 1e-12 * abs(s1["energy"])
+    assert abs(o["energy"] - s2["energy"]) < 1e-12 * abs(s2["energy"])
+    for k in ("d2aa", "d2bb", "d2ab"):
+        assert np.abs(o[k] - s2[k]).max() <= 1e-13 * np.abs(s2[k]).max(), k
