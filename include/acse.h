@@ -486,6 +486,23 @@ acse_status acse_step_spin(acse_ctx ctx, acse_problem_spin *prob, double eps, co
                            double *R_aa, double *R_bb, double *R_ab, double *U_aa, double *U_bb, double *U_ab,
                            double *E_host, double *norm2_host);
 
+/* The Euler iteration of acse_solve (Eq. (9), the method section's stopping
+ * rules) for a state of any S_z: each trial is the step of acse_step_spin at
+ * its step size from the kept state 2D_n (every block at 2D_n's block trace,
+ * both 1-RDMs contracted from the new 2-RDM), its E and ||R||^2 as for
+ * acse_residual_spin.  Controls ACSE_EULER_FIXED and ACSE_EULER_BACKTRACK;
+ * ACSE_EULER_QUADRATIC is ACSE_ERR_UNSUPPORTED (it needs an adjoint of the
+ * spin-block map).  prob's d1a, d1b, d2aa, d2bb and d2ab are overwritten with
+ * the returned state; a rise returns the state before it.  opts, result,
+ * history and capacity as for acse_solve and acse_step_spin (ACSE_FP64 or
+ * ACSE_INT8CRT).  The first call allocates 3 r_max^4 + 2 r_max^2 doubles more
+ * (the kept state), kept until acse_destroy.  Synchronises once per trial.
+ * On an error mid-run the problem arrays hold the last accepted or trial
+ * state. */
+acse_status acse_solve_spin(acse_ctx ctx, acse_problem_spin *prob, const acse_options *opts,
+                            const acse_solve_options *sopts, acse_solve_result *result,
+                            acse_trial *history, int32_t capacity);
+
 /* Energy Tr(K 2D) = <K_s, d2aa> + <K_s, d2bb> + 2 <K_s, d2ab> (Eq. (2), Eq. (6)); the
  * 1-RDM pointers may be NULL.  Synchronises. */
 acse_status acse_energy_spin(acse_ctx ctx, const acse_problem_spin *prob, double *E_host);

@@ -34,7 +34,7 @@ EXPORTS = ("acse_create", "acse_destroy", "acse_set_stream", "acse_residual", "a
            "acse_workspace_bytes", "acse_profile_enable", "acse_profile_read", "acse_autotune",
            "acse_residual_vjp", "acse_energy_vjp", "acse_residual_batched",
            "acse_autotune_batched", "acse_solve", "acse_residual_noalloc", "acse_residual_spin",
-           "acse_step_spin", "acse_energy_spin")
+           "acse_step_spin", "acse_energy_spin", "acse_solve_spin")
 NUM_TILE_CONFIGS = 3
 NUM_STAGES = 8
 STAGES = ("rdm_operands", "fold", "transforms", "gemm", "assembly", "step_tail", "ny_share", "ny_gemm")
@@ -129,6 +129,9 @@ _sig = {
     "acse_step_spin": (ctypes.c_int, [_P, ctypes.POINTER(ProblemSpin), ctypes.c_double, ctypes.POINTER(Options),
                                       _P, _P, _P, _P, _P, _P, _D, _D]),
     "acse_energy_spin": (ctypes.c_int, [_P, ctypes.POINTER(ProblemSpin), _D]),
+    "acse_solve_spin": (ctypes.c_int, [_P, ctypes.POINTER(ProblemSpin), ctypes.POINTER(Options),
+                                       ctypes.POINTER(SolveOptions), ctypes.POINTER(SolveResult),
+                                       ctypes.POINTER(Trial), ctypes.c_int32]),
     "acse_solve": (ctypes.c_int, [_P, ctypes.POINTER(Problem), ctypes.POINTER(Options),
                                   ctypes.POINTER(SolveOptions), ctypes.POINTER(SolveResult),
                                   ctypes.POINTER(Trial), ctypes.c_int32]),
@@ -513,6 +516,32 @@ class Context:
         if return_ru:
             res.update(zip(("R_aa", "R_bb", "R_ab", "U_aa", "U_bb", "U_ab"), outs))
         return res
+
+    def solve_spin_raw(self, prob, opts, sopts, capacity=256):
+        """acse_solve_spin on a prepared problem; returns (SolveResult, [Trial])."""
+        _check_opts(opts, prob.r)
+        res = SolveResult()
+        hist = (Trial * max(1, capacity))()
+        self._check(_lib.acse_solve_spin(self._h, ctypes.byref(prob), ctypes.byref(opts), ctypes.byref(sopts),
+                                         ctypes.byref(res), hist, int(capacity)))
+        return res, [hist[i] for i in range(min(res.trials, capacity))]
+
+    def solve_spin(self, h, V, d1a, d1b, d2aa, d2bb, d2ab, n_alpha, n_beta, eps=1e-3, de_tol=1e-6,
+                   max_iter=100, control="fixed", max_halvings=8, precision="fp64", active=None, tile=-1,
+                   flags=0, capacity=256, moduli=0):
+        """The Euler iteration of ``solve`` for a state of any S_z on device
+        copies of the inputs (acse_solve_spin; controls "fixed" and
+        "backtrack").  Returns a dict with the final d1a, d1b, d2aa, d2bb, d2ab
+        (device) and the fields of ``solve``."""
+        prob, t = self.problem_spin(h, V, d1a, d1b, d2aa, d2bb, d2ab, n_alpha, n_beta)
+        so = SolveOptions(float(eps), float(de_tol), 0.0, int(max_iter),
+                          CONTROLS[control] if isinstance(control, str) else int(control), int(max_halvings), 0)
+        res, hist = self.solve_spin_raw(prob, self.options(precision, active, tile, flags, moduli=moduli), so,
+                                        capacity)
+        return dict(d1a=t[2], d1b=t[3], d2aa=t[4], d2bb=t[5], d2ab=t[6], energy0=res.energy0,
+                    norm2_0=res.norm2_0, energy=res.energy, norm2=res.norm2, eps=res.eps,
+                    iterations=res.iterations, trial_count=res.trials, maps=res.maps, stop=STOP_REASONS[res.stop],
+                    trials=[(q.eps, q.energy, q.norm2, q.step, bool(q.accepted)) for q in hist])
 
     def energy_spin(self, h, V, d2aa, d2bb, d2ab, n_alpha, n_beta):
         """E = Tr(K 2D) for a state of any S_z."""

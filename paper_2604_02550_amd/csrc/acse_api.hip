@@ -2543,6 +2543,10 @@ struct SpinWs {
   int8_t *cres[kSpinOps] = {};
   int *cexp[kSpinOps] = {};
   int8_t *cy = nullptr;
+  // the state 2D_n, 1D_n kept while the Euler driver runs its trials
+  // (allocated by the first acse_solve_spin call)
+  void *kbase = nullptr;
+  double *Nk[3] = {}, *gk[2] = {};
 };
 
 acse_status ensure_spin_ws(acse_ctx c, SpinWs *&out) {
@@ -3167,10 +3171,160 @@ extern "C" acse_status acse_step_spin(acse_ctx ctx, acse_problem_spin *prob, dou
   return ACSE_OK;
 }
 
+// Euler iteration of a state of any S_z: the driver of acse_solve with the
+// spin-block residual map, the per-block trace restoration and the 1-RDM per
+// spin (FIXED and BACKTRACK controls).
+extern "C" acse_status acse_solve_spin(acse_ctx ctx, acse_problem_spin *prob, const acse_options *opts,
+                                       const acse_solve_options *so, acse_solve_result *res, acse_trial *hist,
+                                       int32_t cap) {
+  acse_status st = validate_spin(ctx, prob, opts, true);
+  if (st != ACSE_OK) return st;
+  if ((st = check_solve_options(ctx, so, res, hist, cap)) != ACSE_OK) return st;
+  if (so->control == ACSE_EULER_QUADRATIC)
+    return fail(ctx, ACSE_ERR_UNSUPPORTED, "the spin-block iteration takes the FIXED or BACKTRACK control (the "
+                                           "quadratic control needs an adjoint of the spin-block map)");
+  HIP_TRY(ctx, hipSetDevice(ctx->device));
+  SpinWs *wp = nullptr;
+  if ((st = ensure_spin_ws(ctx, wp)) != ACSE_OK) return st;
+  SpinWs &w = *wp;
+  if (ctx->crt_moduli && (st = ensure_spin_crt(ctx, w)) != ACSE_OK) return st;
+  if (!w.kbase) {
+    const int64_t rm2 = (int64_t)ctx->r_max * ctx->r_max;
+    const int64_t nat = round_up(rm2 * rm2 * 8, 256), sm = round_up(rm2 * 8, 256);
+    if (hipMalloc(&w.kbase, 3 * nat + 2 * sm) != hipSuccess) {
+      (void)hipGetLastError();
+      w.kbase = nullptr;
+      return fail(ctx, ACSE_ERR_NOMEM, "cannot allocate the spin-block driver workspace");
+    }
+    char *q = static_cast<char *>(w.kbase);
+    for (int k = 0; k < 3; ++k, q += nat) w.Nk[k] = reinterpret_cast<double *>(q);
+    for (int k = 0; k < 2; ++k, q += sm) w.gk[k] = reinterpret_cast<double *>(q);
+  }
+  hipStream_t s = ctx->stream;
+  const int r = prob->r;
+  const int N = prob->n_alpha + prob->n_beta;
+  const int64_t r2 = (int64_t)r * r, n4 = r2 * r2;
+  bool masked = false;
+  const ActiveBits act = make_bits(opts, r, &masked);
+  double *d2[3] = {prob->d2aa, prob->d2bb, prob->d2ab};
+  double *d1[2] = {prob->d1a, prob->d1b};
+  double *traces = w.scal + 16;  // input traces of 2D_n's blocks, then U_n's
+
+  *res = acse_solve_result{};
+  auto record = [&](double x, double E, double f, int n) -> int32_t {
+    const int32_t id = res->trials++;
+    if (id < cap) hist[id] = acse_trial{x, E, f, n, 0};
+    return id;
+  };
+  auto mark = [&](int32_t id) { if (id >= 0 && id < cap) hist[id].accepted = 1; };
+  // residual of the problem arrays into w.R (masked copy into w.Rm), its
+  // ||R||^2 and the energy; the map's operands of this state stay in place
+  auto residual = [&](double *f, double *E) -> acse_status {
+    acse_status q;
+    if ((q = spin_prep(ctx, w, prob)) != ACSE_OK) return q;
+    if ((q = spin_xa_from_fold(ctx, w, r)) != ACSE_OK) return q;
+    if ((q = spin_map(ctx, w, r, prob->d1a, prob->d1b, -1.0, w.R, masked ? &act : nullptr,
+                      masked ? w.Rm : nullptr, 0)) != ACSE_OK)
+      return q;
+    ++res->maps;
+    if ((q = spin_energy(ctx, w, prob, 6)) != ACSE_OK) return q;
+    double v[9];
+    if ((q = spin_fetch(ctx, w, v, 9)) != ACSE_OK) return q;
+    *f = v[0] + v[1] + 4.0 * v[2];
+    *E = 2.0 * (v[6] + v[7]) + 4.0 * v[8];
+    if (!std::isfinite(*f)) return fail(ctx, ACSE_ERR_NONFINITE, "||R||^2 is not finite");
+    if (!std::isfinite(*E)) return fail(ctx, ACSE_ERR_NONFINITE, "energy is not finite");
+    return ACSE_OK;
+  };
+  auto restore = [&](bool with_1rdm) -> acse_status {
+    for (int k = 0; k < 3; ++k) HIP_TRY(ctx, hipMemcpyAsync(d2[k], w.Nk[k], n4 * 8, hipMemcpyDeviceToDevice, s));
+    if (with_1rdm)
+      for (int k = 0; k < 2; ++k) HIP_TRY(ctx, hipMemcpyAsync(d1[k], w.gk[k], r2 * 8, hipMemcpyDeviceToDevice, s));
+    return ACSE_OK;
+  };
+  // trial: each block of (2D_n + x U_n) at 2D_n's trace, the 1-RDMs contracted
+  // from it, E' and ||R'||^2
+  auto trial = [&](double x, bool from_kept, double *f, double *E) -> acse_status {
+    acse_status q;
+    if (from_kept && (q = restore(false)) != ACSE_OK) return q;
+    {
+      StageTimer t5(ctx, 5);
+      const double *Uc[3] = {w.U[0], w.U[1], w.U[2]};
+      HIP_TRY(ctx, launch_spin_update(r, x, d2, Uc, traces, s));
+      HIP_TRY(ctx, launch_spin_1rdm(r, N, prob->d2aa, prob->d2bb, prob->d2ab, prob->d1a, prob->d1b, s));
+    }
+    return residual(f, E);
+  };
+
+  {
+    StageTimer t1(ctx, 1);
+    HIP_TRY(ctx, launch_fold(r, N, prob->h, prob->V, ctx->ws.Aaa, ctx->ws.Aab, s));
+  }
+  double E = 0.0, f = 0.0;
+  if ((st = residual(&f, &E)) != ACSE_OK) return st;
+  res->energy0 = res->energy = E;
+  res->norm2_0 = res->norm2 = f;
+  res->stop = ACSE_STOP_MAX_ITER;
+  double e = so->eps;
+
+  for (int n = 0; n < so->max_iter; ++n) {
+    // U_n = F(R_m) on the operands of 2D_n (left in place by its residual)
+    const double *const *Xm = masked ? w.Rm : w.R;
+    if ((st = spin_xa_from_blocks(ctx, w, r, Xm[0], Xm[1], Xm[2])) != ACSE_OK) return st;
+    if ((st = spin_map(ctx, w, r, prob->d1a, prob->d1b, 1.0, w.U, nullptr, nullptr, 3)) != ACSE_OK) return st;
+    ++res->maps;
+    // keep 2D_n and 1D_n; the block traces the trials restore
+    for (int k = 0; k < 3; ++k) HIP_TRY(ctx, hipMemcpyAsync(w.Nk[k], d2[k], n4 * 8, hipMemcpyDeviceToDevice, s));
+    for (int k = 0; k < 2; ++k) HIP_TRY(ctx, hipMemcpyAsync(w.gk[k], d1[k], r2 * 8, hipMemcpyDeviceToDevice, s));
+    {
+      const double *tr_in[6] = {d2[0], d2[1], d2[2], w.U[0], w.U[1], w.U[2]};
+      HIP_TRY(ctx, launch_pair_traces(r, 6, tr_in, traces, s));
+    }
+
+    auto ok = [&](double Et, double ft) { return Et <= E && ft <= f; };
+    double xc = e, fc = 0.0, Ec = 0.0;
+    if ((st = trial(xc, false, &fc, &Ec)) != ACSE_OK) return st;
+    int32_t idc = record(xc, Ec, fc, n);
+    bool chosen = ok(Ec, fc);
+    double last_E = Ec;
+    double cand = e;
+    for (int hv = 0; !chosen && so->control == ACSE_EULER_BACKTRACK && hv < so->max_halvings; ++hv) {
+      cand *= 0.5;
+      double ft = 0.0, Et = 0.0;
+      if ((st = trial(cand, true, &ft, &Et)) != ACSE_OK) return st;
+      const int32_t id = record(cand, Et, ft, n);
+      last_E = Et;
+      if (ok(Et, ft)) { chosen = true; xc = cand; fc = ft; Ec = Et; idc = id; }
+    }
+    if (!chosen) {
+      // keep the state before the rise
+      if ((st = restore(true)) != ACSE_OK) return st;
+      HIP_TRY(ctx, hipStreamSynchronize(s));
+      res->stop = last_E > E ? ACSE_STOP_ENERGY_ROSE : ACSE_STOP_NORM_ROSE;
+      break;
+    }
+    mark(idc);
+    const double dE = Ec - E;
+    E = Ec;
+    f = fc;
+    e = xc;
+    res->iterations = n + 1;
+    res->eps = xc;
+    res->energy = E;
+    res->norm2 = f;
+    if (std::fabs(dE) < so->de_tol) {
+      res->stop = ACSE_STOP_CONVERGED;
+      break;
+    }
+  }
+  return ACSE_OK;
+}
+
 namespace {
 void release_spin_ws(acse_ctx c) {
   SpinWs *w = static_cast<SpinWs *>(c->spws);
   if (w && w->cbase) (void)hipFree(w->cbase);
+  if (w && w->kbase) (void)hipFree(w->kbase);
   delete w;
   c->spws = nullptr;
 }
