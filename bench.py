@@ -56,7 +56,7 @@ def parse():
     ap.add_argument("--modes", default="int8crt,fp64,fp32,bf16x3")
     ap.add_argument("--eps", type=float, default=1e-3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--vjp-modes", default="fp64,fp32",
+    ap.add_argument("--vjp-modes", default="int8crt,fp64,fp32",
                     help="precisions of the adjoint (VJP) measurement ('' to skip)")
     ap.add_argument("--batched-modes", default="int8crt,fp64,fp32",
                     help="precisions of the batched-instances measurement ('' to skip)")
@@ -233,6 +233,43 @@ def bench_solve(acse, ctx, prob, work, pristine, torch, controls, iters, eps, st
                             eps0=eps, acse_step_ms=step_ms)
     for w, q in zip(work, pristine):
         w.copy_(q)
+    return res
+
+
+def bench_solve_spin(acse, ctx, gen, torch, controls, iters, eps, step_ms, name="r50s"):
+    """acse_solve_spin (the Euler iteration for a state of any S_z, FP64) with
+    the fixed and backtracking controls on the open-shell workload, each from
+    the state whose 1-RDMs are contracted from its 2-RDM (one acse_step_spin
+    with eps = 0): wall time per accepted step and per map against the plain
+    acse_step_spin time."""
+    dev = torch.device("cuda", 0)
+    p = gen.named_spin(name)
+    r = p["r"]
+    h = torch.as_tensor(p["h"], device=dev).contiguous()
+    V = torch.as_tensor(p["V"], device=dev).contiguous()
+    work = [torch.as_tensor(p[k], device=dev).contiguous() for k in ("gamma_a", "gamma_b", "d2aa", "d2bb", "d2ab")]
+    pristine = [t.clone() for t in work]
+    prob = acse.ProblemSpin(r, p["Na"], p["Nb"], h.data_ptr(), V.data_ptr(), *[t.data_ptr() for t in work])
+    opts = acse.Context.options("fp64")
+    res = {}
+    for control in controls:
+        if control not in ("fixed", "backtrack"):
+            continue
+        for w, q in zip(work, pristine):
+            w.copy_(q)
+        ctx.step_spin_raw(prob, 0.0, opts, want=False)
+        so = acse.SolveOptions(eps, 0.0, 0.0, iters, acse.CONTROLS[control], 8, 0)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        out, trials = ctx.solve_spin_raw(prob, opts, so)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        res[control] = dict(iterations=out.iterations, trials=out.trials, maps=out.maps,
+                            stop=acse.STOP_REASONS[out.stop], wall_ms=wall * 1e3,
+                            ms_per_accepted_step=wall * 1e3 / max(1, out.iterations),
+                            ms_per_map=wall * 1e3 / max(1, out.maps), energy0=out.energy0, energy=out.energy,
+                            norm2_ratio=out.norm2 / out.norm2_0, eps_last=out.eps, eps0=eps,
+                            acse_step_spin_ms=step_ms)
     return res
 
 
@@ -633,6 +670,10 @@ def main():
     if args.spin_steps > 0:
         line["non_singlet"] = {m: bench_spin(acse, ctx, gen, torch, args.spin_steps, min(args.warmup, 2), args.eps, m)
                                for m in ("int8crt", "fp64")}
+        if args.solve_controls:
+            line["non_singlet"]["solve_fp64"] = bench_solve_spin(
+                acse, ctx, gen, torch, args.solve_controls.split(","), args.solve_iters, args.solve_eps,
+                line["non_singlet"]["fp64"]["ms_per_step"])
     if args.vjp_modes:
         line["vjp"] = bench_vjp(acse, gen, torch, args.vjp_modes.split(","), max(3, args.steps // 2),
                                 args.warmup)

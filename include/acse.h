@@ -93,12 +93,12 @@ typedef enum {
                       product is rebuilt by the Chinese remainder theorem in FP64.  The
                       only rounding is that of the operands to k bits relative to their
                       row's largest magnitude.  Residual, update map, step, autotune
-                      and the Euler iteration (fixed and backtracking controls), with
-                      the Valdemoro or the NY reconstruction, the spin-block calls and
-                      the batched residual on its lanes (one residue workspace per lane,
-                      allocated by the first such batch); the adjoint, the quadratic
-                      control, the persistent batch and acse_residual_noalloc are
-                      ACSE_ERR_UNSUPPORTED with it.  The first
+                      and the Euler iteration (every control; the quadratic one through
+                      the adjoint), with the Valdemoro or the NY reconstruction, the
+                      residual adjoint (Valdemoro), the spin-block calls and the batched
+                      residual on its lanes (one residue workspace per lane, allocated
+                      by the first such batch); the persistent batch and
+                      acse_residual_noalloc are ACSE_ERR_UNSUPPORTED with it.  The first
                       call allocates residue buffers for r_max: 12 x (15 x op_rows x
                       round_up(r_max^2, 256) + 4 op_rows) bytes for the operands
                       (op_rows = r_max^2 rounded up to 256) and 15 x about 4.5 r_max^4
@@ -323,9 +323,13 @@ acse_status acse_solve(acse_ctx ctx, acse_problem *prob, const acse_options *opt
  * antisymmetric in both pairs and Hermitian; d2ab Hermitian and symmetric
  * under (pq)(rs) -> (qp)(sr)), which is what finite differences along
  * symmetry-respecting directions measure.  The contractions run in
- * opts->precision; accumulation of the gradients is FP64.  The first call
- * allocates the adjoint workspace (36 r_max^4 doubles plus 12 pair-index
- * operand buffers), kept until acse_destroy.  Errors as acse_residual. */
+ * opts->precision (with ACSE_INT8CRT the adjoint products are int8
+ * exact-accumulation products of FP64 operands, as in the forward map);
+ * accumulation of the gradients is FP64.  The first call allocates the
+ * adjoint workspace (36 r_max^4 doubles plus 12 pair-index operand buffers),
+ * the first ACSE_INT8CRT call the residues of those 12 buffers and of one
+ * launch's products; both are kept until acse_destroy.  Errors as
+ * acse_residual; the NY reconstruction is ACSE_ERR_UNSUPPORTED. */
 acse_status acse_residual_vjp(acse_ctx ctx, const acse_problem *prob, const acse_options *opts,
                               const double *Rbar_aa, const double *Rbar_ab, double *h_bar,
                               double *V_bar, double *d1_bar, double *d2aa_bar, double *d2ab_bar);

@@ -105,6 +105,12 @@ struct acse_ctx_s {
   double *vnat[36] = {};
   char *vop[12] = {};
   double *vsmall = nullptr;  // gb, tb, fb, I, hb_raw (r_max^2 each)
+  // residues and row exponents of the adjoint's operand buffers and the
+  // residues of one launch's products, for the int8 products (first such call)
+  void *vcbase = nullptr;
+  int8_t *vcres[12] = {};
+  int *vcexp[12] = {};
+  int8_t *vcy = nullptr;
   // Euler driver workspace (allocated by the first acse_solve call)
   void *sbase = nullptr;
   int64_t sbytes = 0;
@@ -1089,6 +1095,7 @@ acse_status acse_destroy(acse_ctx ctx) {
   for (auto &q : ctx->recs) { (void)hipEventDestroy(q.a); (void)hipEventDestroy(q.b); }
   for (auto e : ctx->pool) (void)hipEventDestroy(e);
   if (ctx->vbase) (void)hipFree(ctx->vbase);
+  if (ctx->vcbase) (void)hipFree(ctx->vcbase);
   if (ctx->sbase) (void)hipFree(ctx->sbase);
   if (ctx->nybase) (void)hipFree(ctx->nybase);
   if (ctx->cw.base) (void)hipFree(ctx->cw.base);
@@ -1396,6 +1403,36 @@ acse_status ensure_vjp_ws(acse_ctx c) {
   return ACSE_OK;
 }
 
+// Residue workspace of the adjoint's operand buffers (first int8 call) and
+// the moduli table of the call in progress.
+acse_status ensure_vjp_crt(acse_ctx c) {
+  if (!c->vcbase) {
+    const int rm = c->r_max;
+    const int64_t r2 = (int64_t)rm * rm;
+    const int64_t rbytes = round_up((int64_t)kMaxModuli * op_rows(rm) * crt_ldr((int)r2), 256);
+    const int64_t ebytes = round_up(op_rows(rm) * (int64_t)sizeof(int), 256);
+    const int64_t ybytes = round_up(6 * (int64_t)kMaxModuli * crt_residue_out_bytes((int)r2, (int)r2), 256);
+    const int64_t bytes = 12 * (rbytes + ebytes) + ybytes;
+    if (hipMalloc(&c->vcbase, bytes) != hipSuccess) {
+      (void)hipGetLastError();
+      c->vcbase = nullptr;
+      return fail(c, ACSE_ERR_NOMEM, "cannot allocate the int8 residue workspace of the adjoint (" +
+                                         std::to_string(bytes) + " bytes)");
+    }
+    char *q = static_cast<char *>(c->vcbase);
+    for (int k = 0; k < 12; ++k) {
+      c->vcres[k] = reinterpret_cast<int8_t *>(q);
+      q += rbytes;
+      c->vcexp[k] = reinterpret_cast<int *>(q);
+      q += ebytes;
+    }
+    c->vcy = reinterpret_cast<int8_t *>(q);
+  }
+  if (c->crt.nmod != c->crt_moduli && !crt_table(c->crt_moduli, c->crt))
+    return fail(c, ACSE_ERR_ARG, "no moduli table for " + std::to_string(c->crt_moduli) + " moduli");
+  return ACSE_OK;
+}
+
 struct Nat4 {
   int64_t S[4];
   explicit Nat4(int r) {
@@ -1417,8 +1454,6 @@ extern "C" acse_status acse_residual_vjp(acse_ctx ctx, const acse_problem *prob,
   acse_status st = validate(ctx, prob, opts);
   if (st != ACSE_OK) return st;
   if (ctx->ny_on) return fail(ctx, ACSE_ERR_UNSUPPORTED, "the adjoint is built for the Valdemoro reconstruction only");
-  if (ctx->crt_moduli)
-    return fail(ctx, ACSE_ERR_UNSUPPORTED, "the adjoint runs in FP64, FP32 or split BF16, not in int8 exact accumulation");
   for (const void *q : {static_cast<const void *>(Rbar_aa), static_cast<const void *>(Rbar_ab),
                         static_cast<const void *>(h_bar), static_cast<const void *>(V_bar),
                         static_cast<const void *>(d1_bar), static_cast<const void *>(d2aa_bar),
@@ -1426,13 +1461,17 @@ extern "C" acse_status acse_residual_vjp(acse_ctx ctx, const acse_problem *prob,
     if ((st = check_out(ctx, q, "VJP array")) != ACSE_OK) return st;
   HIP_TRY(ctx, hipSetDevice(ctx->device));
   if ((st = ensure_vjp_ws(ctx)) != ACSE_OK) return st;
+  // int8 exact accumulation: every operand is built in FP64 and converted to
+  // residues before its grouped launch
+  const bool crt = ctx->crt_moduli != 0;
+  if (crt && (st = ensure_vjp_crt(ctx)) != ACSE_OK) return st;
 
   const int r = prob->r;
   const int N = prob->n_alpha + prob->n_beta;
   const int64_t r2 = (int64_t)r * r, r3 = r2 * r;
   const int ld = (int)op_ld(r);
   const int64_t Mp = op_rows(r);
-  const GemmPrec prec = prec_of(opts);
+  const GemmPrec prec = crt ? GEMM_F64 : prec_of(opts);
   const double *g = prob->d1;
   Workspace &w = ctx->ws;
   hipStream_t s = ctx->stream;
@@ -1522,8 +1561,10 @@ extern "C" acse_status acse_residual_vjp(acse_ctx ctx, const acse_problem *prob,
                         gb, 1));
   HIP_TRY(ctx, launch_vjp_pe(r, Sbaa, Sbab, Ppb, Pmb, E3b, s));
 
+  int kdim[kMaxGemmProbs] = {};  // K of each product of the batch being built
   auto gemm_set = [&](GemmBatch &b, int q, int ia, int ib, double alpha, double *C, const int om[4]) {
     GemmProb &P = b.p[q];
+    kdim[q] = (int)r2;
     OperandRef a = vop(ia), bb = vop(ib);
     P.A = a.hi; P.A2 = a.lo; P.B = bb.hi; P.B2 = bb.lo;
     P.C = C; P.alpha = alpha;
@@ -1537,6 +1578,76 @@ extern "C" acse_status acse_residual_vjp(acse_ctx ctx, const acse_problem *prob,
     auto it = ctx->tuned.find({r, (int)prec});
     use_cfg = it != ctx->tuned.end() ? it->second : gemm_default_cfg(prec, (int)r2, (int)r2);
   }
+  // one grouped launch of adjoint products: on the tiles of the call's
+  // precision, or (int8 exact accumulation) the residues of every operand
+  // buffer the batch reads, the modular products (reconstruction factors in
+  // their epilogue) and the reconstruction through the same store maps
+  auto vop_index = [&](const void *p) {
+    for (int q = 0; q < 12; ++q)
+      if (ctx->vop[q] == p) return q;
+    return -1;
+  };
+  auto vjp_gemm = [&](GemmBatch &b) -> acse_status {
+    if (!crt) {
+      HIP_TRY(ctx, gemm_launch(prec, use_cfg, b, s));
+      return ACSE_OK;
+    }
+    int bk[12] = {}, brows[12] = {}, bld[12] = {};
+    int ia[kMaxGemmProbs] = {}, ib[kMaxGemmProbs] = {};
+    for (int k = 0; k < b.count; ++k) {
+      const GemmProb &P = b.p[k];
+      ia[k] = vop_index(P.A);
+      ib[k] = vop_index(P.B);
+      if (ia[k] < 0 || ib[k] < 0) return fail(ctx, ACSE_ERR_HIP, "adjoint product operand outside its buffers");
+      for (int side = 0; side < 2; ++side) {
+        const int q = side ? ib[k] : ia[k];
+        if (bk[q] && bk[q] != kdim[k]) return fail(ctx, ACSE_ERR_HIP, "adjoint operand buffer read with two K");
+        bk[q] = kdim[k];
+        bld[q] = P.ld;
+        brows[q] = std::max(brows[q], side ? P.N : P.M);
+      }
+    }
+    ResidueBatch rb{};
+    int nrows = 0;
+    for (int q = 0; q < 12; ++q) {
+      if (!bk[q]) continue;
+      ResidueJob &J = rb.job[rb.count++];
+      J.src = reinterpret_cast<const double *>(ctx->vop[q]);
+      J.dst = ctx->vcres[q];
+      J.e = ctx->vcexp[q];
+      J.plane = Mp * crt_ldr(bk[q]);
+      J.row_begin = nrows;
+      J.K = bk[q];
+      J.ld = bld[q];
+      J.ldr = (int)crt_ldr(bk[q]);
+      J.kbits = crt_kbits(ctx->crt, bk[q]);
+      J.premul = 0;
+      nrows += brows[q];
+    }
+    rb.total_rows = nrows;
+    HIP_TRY(ctx, launch_to_residues(rb, ctx->crt, s));
+    int64_t yoff = 0;  // the products' residues one after another (their sizes differ)
+    for (int k = 0; k < b.count; ++k) {
+      GemmProb &G = b.p[k];
+      const int K = kdim[k];
+      G.A = ctx->vcres[ia[k]];
+      G.B = ctx->vcres[ib[k]];
+      G.A2 = G.B2 = nullptr;
+      G.ld = G.Kp = (int)crt_ldr(K);
+      G.kchunk = G.Kp;
+      G.plane_a = G.plane_b = Mp * crt_ldr(K);
+      G.ea = ctx->vcexp[ia[k]];
+      G.eb = ctx->vcexp[ib[k]];
+      G.kshift = 2 * crt_kbits(ctx->crt, K);
+      G.u_out = 1;
+      G.plane_y = crt_residue_out_bytes(G.M, G.N);
+      G.Y = ctx->vcy + yoff;
+      yoff += (int64_t)ctx->crt.nmod * G.plane_y;
+    }
+    HIP_TRY(ctx, gemm_crt_launch(b, ctx->crt, s));
+    HIP_TRY(ctx, crt_combine_launch(b, ctx->crt, s));
+    return ACSE_OK;
+  };
   {  // particle-hole adjoint products
     // L+b[(k,i),(p,s)] = sum_(j,l) P+b[i,j,k,l] R+[j,l,p,s];  R+b[(j,l),(p,s)] = sum_(k,i) P+b L+[k,i,p,s]
     const int Akijl[4] = {2, 0, 1, 3}, Ajlki[4] = {1, 3, 2, 0};
@@ -1576,7 +1687,7 @@ extern "C" acse_status acse_residual_vjp(acse_ctx ctx, const acse_problem *prob,
     gemm_set(b, 3, 6, 7, 1.0, Rmb, ID);
     gemm_set(b, 4, 8, 9, -2.0, L3b, ID);
     gemm_set(b, 5, 10, 11, -2.0, R3b, ID);
-    HIP_TRY(ctx, gemm_launch(prec, use_cfg, b, s));
+    if ((st = vjp_gemm(b)) != ACSE_OK) return st;
   }
   {  // particle-particle adjoint products
     // G-bar = Z-bar B^T-products:  Gb[(ij),(rs)] = sum_(kl) Sb[ij,kl] B[kl,rs]
@@ -1622,6 +1733,7 @@ extern "C" acse_status acse_residual_vjp(acse_ctx ctx, const acse_problem *prob,
       GemmProb &P = b.p[q];
       OperandRef a = vop(ia), bb = vop(ib);
       const int K = k_le ? nle : nlt, ldk = (int)(k_le ? ldle : ldlt);
+      kdim[q] = K;
       P.A = a.hi; P.A2 = a.lo; P.B = bb.hi; P.B2 = bb.lo;
       P.C = C; P.alpha = alpha;
       P.M = M; P.N = N; P.Kp = gemm_kp(prec, K, ldk); P.ld = ldk; P.rdiv = 1;
@@ -1674,7 +1786,7 @@ extern "C" acse_status acse_residual_vjp(acse_ctx ctx, const acse_problem *prob,
       gemm_set(b, 3, 6, 8, 2.0, Gbab, ID);
       gemm_set(b, 4, 7, 9, 4.0, Bbab, ID);   // 2 * Gamma2_ab = 4 d2ab
       gemm_set(b, 5, 6, 10, 1.0, Mab, ID);
-      HIP_TRY(ctx, gemm_launch(prec, use_cfg, b, s));
+      if ((st = vjp_gemm(b)) != ACSE_OK) return st;
       HIP_TRY(ctx, launch_unpack_pairs(r, 1, T1, nlt, Gbaa, s));
       HIP_TRY(ctx, launch_unpack_pairs(r, 0, T2, nlt, Bbaa, s));
       HIP_TRY(ctx, launch_unpack_pairs(r, 0, T3, nlt, Maa, s));
@@ -1696,7 +1808,7 @@ extern "C" acse_status acse_residual_vjp(acse_ctx ctx, const acse_problem *prob,
       pair_set(b, 2, 4, 5, 1.0, T3, R2, nlt, 0);
       pair_set(b, 3, 6, 7, 2.0, Gp, nle, nle, 1);
       pair_set(b, 4, 8, 9, 2.0, Gm, nlt, nlt, 0);
-      HIP_TRY(ctx, gemm_launch(prec, use_cfg, b, s));
+      if ((st = vjp_gemm(b)) != ACSE_OK) return st;
       HIP_TRY(ctx, launch_unpack_pairs(r, 1, T1, nlt, Gbaa, s));
       HIP_TRY(ctx, launch_unpack_pairs(r, 0, T2, nlt, Bbaa, s));
       HIP_TRY(ctx, launch_unpack_pairs(r, 0, T3, nlt, Maa, s));
@@ -1722,7 +1834,7 @@ extern "C" acse_status acse_residual_vjp(acse_ctx ctx, const acse_problem *prob,
       pair_set(b, 1, 2, 3, 4.0, Bm, R2, nlt, 0);
       pair_set(b, 2, 4, 5, 1.0, Mp, R2, nle, 1);
       pair_set(b, 3, 6, 7, 1.0, Mm, R2, nlt, 0);
-      HIP_TRY(ctx, gemm_launch(prec, use_cfg, b, s));
+      if ((st = vjp_gemm(b)) != ACSE_OK) return st;
       HIP_TRY(ctx, launch_unpack_pm(r, 0, Bp, nle, Bm, nlt, Bbab, s));
       HIP_TRY(ctx, launch_unpack_pm(r, 0, Mp, nle, Mm, nlt, Mab, s));
     }
@@ -1962,8 +2074,6 @@ extern "C" acse_status acse_solve(acse_ctx ctx, acse_problem *prob, const acse_o
   const bool quad = so->control == ACSE_EULER_QUADRATIC;
   if (quad && ctx->ny_on)
     return fail(ctx, ACSE_ERR_UNSUPPORTED, "the quadratic control needs the adjoint, built for the Valdemoro reconstruction only");
-  if (quad && ctx->crt_moduli)
-    return fail(ctx, ACSE_ERR_UNSUPPORTED, "the quadratic control needs the adjoint, not built for int8 exact accumulation");
   if (ctx->crt_moduli && (st = ensure_crt(ctx)) != ACSE_OK) return st;
   SolveWs sw{};
   if ((st = ensure_solve_ws(ctx, quad, sw)) != ACSE_OK) return st;

@@ -172,18 +172,31 @@ def test_crt_deterministic_and_solve(acse, ctx):
         assert abs(t1[1] - t2[1]) <= 1e-10 * abs(t2[1]) and abs(t1[2] - t2[2]) <= 1e-9 * t2[2]
 
 
+def test_crt_quadratic_solve_takes_the_fp64_decisions(ctx):
+    """The quadratic control in the int8 mode (its slope from the int8
+    adjoint): the FP64 path's trials, decisions and second step sizes."""
+    p = gen.problem(10, 6, 20, seed=2)
+    # start from the 1-RDM contracted from the 2-RDM (an eps = 0 step)
+    s0 = ctx.step(p["h"], p["V"], p["gamma"], p["d2aa"], p["d2ab"], 3, eps=0.0)
+    args = (p["h"], p["V"], cpu(s0["d1"]), cpu(s0["d2aa"]), cpu(s0["d2ab"]), 3)
+    print("[crt] r10 quadratic solve", flush=True)
+    r64 = ctx.solve(*args, eps=1e-3, de_tol=0.0, max_iter=5, control="quadratic")
+    rc = ctx.solve(*args, eps=1e-3, de_tol=0.0, max_iter=5, control="quadratic", precision="int8crt")
+    assert r64["iterations"] >= 3
+    assert rc["stop"] == r64["stop"] and rc["iterations"] == r64["iterations"] and rc["maps"] == r64["maps"]
+    assert [t[3:] for t in rc["trials"]] == [t[3:] for t in r64["trials"]]
+    for t1, t2 in zip(rc["trials"], r64["trials"]):
+        assert abs(t1[0] - t2[0]) <= 1e-8 * abs(t2[0])
+        assert abs(t1[1] - t2[1]) <= 1e-9 * abs(t2[1]) and abs(t1[2] - t2[2]) <= 1e-8 * t2[2]
+
+
 def test_crt_unsupported_combinations(acse, ctx):
     import torch
     p = PROBLEMS["r6"]()
     args = (p["h"], p["V"], p["gamma"], p["d2aa"], p["d2ab"], p["N"] // 2)
-    Rb = gen.cotangent(np.random.default_rng(1), 6)
-    with pytest.raises(acse.AcseError, match="UNSUPPORTED"):
-        ctx.residual_vjp(*args, *Rb, precision="int8crt")
     inst = [dict(h=p["h"], V=p["V"], N=p["N"], gamma=p["gamma"], d2aa=p["d2aa"], d2ab=p["d2ab"])]
     with pytest.raises(acse.AcseError, match="UNSUPPORTED"):
         ctx.residual_batched(inst, precision="int8crt", flags=acse.FLAG_BATCH_PERSISTENT)
-    with pytest.raises(acse.AcseError, match="UNSUPPORTED"):
-        ctx.solve(*args, control="quadratic", precision="int8crt", max_iter=1)
     with pytest.raises(acse.AcseError, match="UNSUPPORTED"):
         acse.residual_noalloc(*args, precision="int8crt")
     for bad in (7, 16, -1):

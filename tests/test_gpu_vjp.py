@@ -6,7 +6,8 @@
   (step 1e-5) of the oracle's FP64 forward along one structured direction per
   input, against <gradient, direction>, FP64 and FP32.
 * FP32 / split-BF16 contractions against the FP64 oracle adjoint, stated
-  per-gradient tolerances.
+  per-gradient tolerances; int8 exact-accumulation products at the FP64 bar
+  (1e-10 against the oracle adjoint, the r = 30 finite differences at 1e-7).
 * The torch.autograd.Function wrappers give the same gradients, and two calls
   are bitwise identical.
 """
@@ -86,7 +87,22 @@ def test_residual_vjp_fp64_vs_oracle(ctx, name):
         assert maxrel(got[k], ref[k]) < TOL64, (k, maxrel(got[k], ref[k]))
 
 
-@pytest.mark.parametrize("precision,tol", [("fp64", TOL64), ("fp32", 1e-5), ("bf16x3", 5e-5)])
+@pytest.mark.parametrize("name", list(PROBLEMS))
+def test_residual_vjp_int8crt_vs_oracle(ctx, name):
+    """The adjoint with int8 exact-accumulation products: the FP64 bar
+    against the oracle adjoint (operands rounded to k = 44+ bits, products
+    exact)."""
+    p = PROBLEMS[name]()
+    print(f"[residual_vjp_int8crt] {name} r={p['r']}", flush=True)
+    Rb = gen.cotangent(np.random.default_rng(22), p["r"])
+    ref = adj.residual_vjp(p["h"], p["V"], p["N"], p["gamma"], p["d2aa"], p["d2ab"], *Rb)
+    got = gpu_vjp(ctx, p, Rb, "int8crt")
+    for k in KEYS:
+        assert rel(got[k], ref[k]) < TOL64, (k, rel(got[k], ref[k]))
+        assert maxrel(got[k], ref[k]) < TOL64, (k, maxrel(got[k], ref[k]))
+
+
+@pytest.mark.parametrize("precision,tol", [("fp64", TOL64), ("fp32", 1e-5), ("bf16x3", 5e-5), ("int8crt", TOL64)])
 def test_residual_vjp_general_kernels(acse, ctx, precision, tol):
     """The adjoint with the general-size kernels (ACSE_FLAG_GENERAL_KERNELS): the
     G2 kernel that stores G2, and the alpha-beta pp adjoint products packed
@@ -144,7 +160,7 @@ def vjp30():
     return p, Rb, dirs, fd
 
 
-@pytest.mark.parametrize("precision,tol", [("fp64", 1e-7), ("fp32", 1e-4)])
+@pytest.mark.parametrize("precision,tol", [("fp64", 1e-7), ("fp32", 1e-4), ("int8crt", 1e-7)])
 def test_residual_vjp_r30_finite_difference(ctx, vjp30, precision, tol):
     p, Rb, dirs, fd = vjp30
     got = gpu_vjp(ctx, p, Rb, precision)
