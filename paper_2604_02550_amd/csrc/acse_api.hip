@@ -2242,7 +2242,12 @@ extern "C" acse_status acse_solve(acse_ctx ctx, acse_problem *prob, const acse_o
 namespace {
 
 constexpr int kMaxBatch = 4096;
-constexpr int kBatchStreams = 4;  // side streams for the per-instance stages
+// Per-instance stages run on kBatchLanes lanes: lane 0 is the context stream,
+// lanes 1.. are side streams.  With HIP's default of four hardware queues per
+// process, the context stream and three side streams each get a queue of
+// their own; a fourth side stream would share one and serialise two lanes.
+constexpr int kBatchLanes = 4;
+constexpr int kSideStreams = kBatchLanes - 1;
 
 struct BatchPlan {
   std::vector<Workspace> ws;
@@ -2315,7 +2320,7 @@ acse_status ensure_batch(acse_ctx c, int count, const acse_problem *probs, Batch
   }
   if (!c->hdesc_done) HIP_TRY(c, hipEventCreateWithFlags(&c->hdesc_done, hipEventDisableTiming));
   if (!c->fork_ev) HIP_TRY(c, hipEventCreateWithFlags(&c->fork_ev, hipEventDisableTiming));
-  for (int q = 0; q < kBatchStreams; ++q) {
+  for (int q = 0; q < kSideStreams; ++q) {
     if (!c->side[q]) HIP_TRY(c, hipStreamCreateWithFlags(&c->side[q], hipStreamNonBlocking));
     if (!c->join_ev[q]) HIP_TRY(c, hipEventCreateWithFlags(&c->join_ev[q], hipEventDisableTiming));
   }
@@ -2348,15 +2353,19 @@ struct StreamSwap {
   ~StreamSwap() { c->stream = saved; }
 };
 
-// The side streams wait for everything enqueued so far on the context stream.
+// Stream of lane l (lane 0: the context stream).
+hipStream_t lane_stream(acse_ctx c, int l) { return l == 0 ? c->stream : c->side[l - 1]; }
+
+// The side streams of lanes 1 .. ns-1 wait for everything enqueued so far on
+// the context stream (lane 0).
 acse_status fork_sides(acse_ctx c, int ns) {
   HIP_TRY(c, hipEventRecord(c->fork_ev, c->stream));
-  for (int q = 0; q < ns; ++q) HIP_TRY(c, hipStreamWaitEvent(c->side[q], c->fork_ev, 0));
+  for (int q = 0; q + 1 < ns; ++q) HIP_TRY(c, hipStreamWaitEvent(c->side[q], c->fork_ev, 0));
   return ACSE_OK;
 }
-// The context stream waits for everything enqueued so far on the side streams.
+// The context stream waits for everything enqueued so far on those side streams.
 acse_status join_sides(acse_ctx c, int ns) {
-  for (int q = 0; q < ns; ++q) {
+  for (int q = 0; q + 1 < ns; ++q) {
     HIP_TRY(c, hipEventRecord(c->join_ev[q], c->side[q]));
     HIP_TRY(c, hipStreamWaitEvent(c->stream, c->join_ev[q], 0));
   }
@@ -2391,7 +2400,7 @@ acse_status run_lanes(acse_ctx c, int count, const acse_problem *probs, GemmPrec
   auto one = [&](int i) -> acse_status {
     const acse_problem *p = &probs[i];
     Workspace &w = plan.ws[i];
-    StreamSwap sw(c, c->side[lane[i]]);
+    StreamSwap sw(c, lane_stream(c, lane[i]));
     acse_status s2 = prep_rdm_operands(c, p, prec, w);
     if (s2 != ACSE_OK) return s2;
     {
@@ -2432,12 +2441,12 @@ acse_status run_lanes(acse_ctx c, int count, const acse_problem *probs, GemmPrec
 acse_status run_batched(acse_ctx c, int count, const acse_problem *probs, GemmPrec prec, int cfg,
                         double *const *Raa, double *const *Rab, BatchPlan &plan, bool persistent, int tile) {
   acse_status st;
-  const int ns = std::min(count, kBatchStreams);
+  const int ns = std::min(count, kBatchLanes);
   std::vector<int> order(count), lane(count);
   for (int i = 0; i < count; ++i) order[i] = i;
   std::stable_sort(order.begin(), order.end(),
                    [&](int a, int b) { return probs[a].r > probs[b].r; });
-  double load[kBatchStreams] = {};
+  double load[kBatchLanes] = {};
   for (int i : order) {
     int best = 0;
     for (int q = 1; q < ns; ++q)
@@ -2453,7 +2462,7 @@ acse_status run_batched(acse_ctx c, int count, const acse_problem *probs, GemmPr
   auto front = [&](int i) -> acse_status {
     const acse_problem *p = &probs[i];
     Workspace &w = plan.ws[i];
-    StreamSwap sw(c, c->side[lane[i]]);
+    StreamSwap sw(c, lane_stream(c, lane[i]));
     acse_status s2 = prep_rdm_operands(c, p, prec, w);
     if (s2 != ACSE_OK) return s2;
     {
@@ -2494,7 +2503,7 @@ acse_status run_batched(acse_ctx c, int count, const acse_problem *probs, GemmPr
   }
   if ((st = fork_sides(c, ns)) != ACSE_OK) return st;
   for (int i : order) {
-    StreamSwap sw(c, c->side[lane[i]]);
+    StreamSwap sw(c, lane_stream(c, lane[i]));
     if ((st = map_back(c, &probs[i], -1.0, Raa ? Raa[i] : plan.ws[i].Raa,
                        Rab ? Rab[i] : plan.ws[i].Rab, none, nullptr, nullptr, plan.norms + i,
                        plan.ws[i])) != ACSE_OK)
