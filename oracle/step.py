@@ -124,29 +124,40 @@ def energy_spin(h, V, Na, Nb, d2aa, d2bb, d2ab):
     return float(np.sum(K * d2))
 
 
-def residual_spin(h, V, Na, Nb, ga, gb, d2aa, d2bb, d2ab):
+def sigma_open_shell(r, Na, Nb):
+    """Spin-orbital NY weights of the open-shell Hartree-Fock reference: alpha
+    orbitals below Na and beta orbitals below Nb occupied (+1), the rest -1;
+    alpha orbitals first."""
+    p = np.arange(r)
+    return np.concatenate([np.where(p < Na, 1.0, -1.0), np.where(p < Nb, 1.0, -1.0)])
+
+
+def residual_spin(h, V, Na, Nb, ga, gb, d2aa, d2bb, d2ab, sigma_so=None):
     """R = F(K) (Eq. (4)) of a state of any S_z; returns (R_aa, R_bb, R_ab,
-    ||R||^2 over spin orbitals)."""
+    ||R||^2 over spin orbitals).  ``sigma_so`` (2r weights, alpha orbitals
+    first, +1 occupied / -1 unoccupied in the reference) selects the NY 3-RDM
+    (Eq. (8)); None is Valdemoro."""
     K = rdm.reduced_hamiltonian(h, V, Na + Nb)
     d1, d2 = rdm.spin_blocks_to_spin_orbital(ga, gb, d2aa, d2bb, d2ab)
-    R = residual_map(K, d1, d2, hermitian=True).numpy()
+    R = residual_map(K, d1, d2, hermitian=True, sigma_so=sigma_so).numpy()
     raa, rbb, rab = rdm.spin_orbital_to_spin_blocks(R)
     return raa, rbb, rab, norm2_spin_orbital(R)
 
 
-def step_spin(h, V, Na, Nb, ga, gb, d2aa, d2bb, d2ab, eps, active=None, keep_spin_orbital=False):
+def step_spin(h, V, Na, Nb, ga, gb, d2aa, d2bb, d2ab, eps, active=None, keep_spin_orbital=False, sigma_so=None):
     """One Euler step (Eq. (9)) of a state of any S_z, with the readings of
     ``step`` (mask, trace restoration per spin block, 1-RDM contraction); the
-    1-RDM blocks after the step are those of the contraction of the new 2-RDM."""
+    1-RDM blocks after the step are those of the contraction of the new 2-RDM.
+    ``sigma_so`` as for ``residual_spin`` (both maps of the step)."""
     r = h.shape[0]
     N = Na + Nb
     K = rdm.reduced_hamiltonian(h, V, N)
     d1, d2 = rdm.spin_blocks_to_spin_orbital(ga, gb, d2aa, d2bb, d2ab)
-    R = residual_map(K, d1, d2, hermitian=True).numpy()
+    R = residual_map(K, d1, d2, hermitian=True, sigma_so=sigma_so).numpy()
     n2 = norm2_spin_orbital(R)
     mask = active_mask(active, r)
     Rm = R if mask is None else R * mask
-    U = residual_map(Rm, d1, d2, hermitian=False).numpy()
+    U = residual_map(Rm, d1, d2, hermitian=False, sigma_so=sigma_so).numpy()
     raa, rbb, rab = rdm.spin_orbital_to_spin_blocks(R)
     uaa, ubb, uab = rdm.spin_orbital_to_spin_blocks(U)
     traces = tuple(_trace(b) for b in (d2aa, d2bb, d2ab))

@@ -188,3 +188,46 @@ def test_step_spin_blocks_of_fewer_than_two_electrons_stay_zero(Na, Nb):
     for k in ("d2aa", "d2ab"):
         assert abs(tr(o[k]) - tr(p[k])) < 1e-13 * max(1.0, abs(tr(p[k])))
     assert np.all(np.isfinite(o["d2aa"])) and np.isfinite(o["energy"])
+
+
+def test_spin_blocks_ny_on_singlet_inputs_is_the_singlet_ny_map():
+    """The spin-block NY residual and step, given a singlet as three blocks and
+    both spins' weights from the spatial ones, are the singlet NY ones (whose
+    cumulant formula is pinned to the exact second-order 3-cumulant)."""
+    p = gen.problem(6, 4, 12, seed=5)
+    sig = np.array([1.0, 1.0, -1.0, 1.0, -1.0, -1.0])  # not a prefix
+    sso = np.concatenate([sig, sig])
+    args = (p["h"], p["V"], 2, 2, p["gamma"], p["gamma"], p["d2aa"], p["d2aa"], p["d2ab"])
+    raa, rbb, rab, n2 = st.residual_spin(*args, sigma_so=sso)
+    Raa, Rab = st.residual(p["h"], p["V"], 4, p["gamma"], p["d2aa"], p["d2ab"], sigma=sig)[:2]
+    assert np.abs(raa - Raa).max() < 1e-12 * np.abs(Raa).max()
+    assert np.abs(rbb - Raa).max() < 1e-12 * np.abs(Raa).max()
+    assert np.abs(rab - Rab).max() < 1e-12 * np.abs(Rab).max()
+    v = st.residual_spin(*args)
+    assert np.abs(v[0] - raa).max() > 1e-6 * np.abs(raa).max()  # NY differs from V here
+    o = st.step_spin(*args, 1e-3, sigma_so=sso)
+    s1 = st.step(p["h"], p["V"], 4, p["gamma"], p["d2aa"], p["d2ab"], 1e-3, sigma=sig)
+    assert abs(o["energy"] - s1["energy"]) < 1e-12 * abs(s1["energy"])
+    assert np.abs(o["d2aa"] - s1["d2aa"]).max() < 1e-12 * np.abs(s1["d2aa"]).max()
+
+
+@pytest.mark.parametrize("r,Na,Nb", [(4, 3, 1), (4, 1, 3), (5, 3, 2)])
+def test_spin_blocks_ny_equals_v_for_a_determinant(r, Na, Nb):
+    """For an open-shell determinant the 2-cumulant vanishes, so the NY
+    3-cumulant does too and the NY residual is the (exact) Valdemoro one,
+    whatever the weights."""
+    rng = np.random.default_rng(r + 10 * Na)
+    fock = fm.Fock(2 * r)
+    Ua, Ub = gen.haar_orthogonal(rng, r), gen.haar_orthogonal(rng, r)
+    C = np.zeros((2 * r, Na + Nb))
+    C[:r, :Na] = Ua[:, :Na]
+    C[r:, Na:] = Ub[:, :Nb]
+    psi = fm.rotated_determinant(fock, C)
+    h, V = gen.hamiltonian(rng, r, 6)
+    ga, gb, aa, bb, ab = fm.spin_blocks_from_state(fock, psi)
+    args = (h, V, Na, Nb, ga, gb, aa, bb, ab)
+    v = st.residual_spin(*args)
+    for sso in (st.sigma_open_shell(r, Na, Nb), -st.sigma_open_shell(r, Na, Nb)):
+        n = st.residual_spin(*args, sigma_so=sso)
+        for a, b in zip(n[:3], v[:3]):
+            assert np.abs(a - b).max() <= 1e-11 * max(np.abs(v[0]).max(), np.abs(v[2]).max(), 1e-300)
