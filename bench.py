@@ -67,6 +67,8 @@ def parse():
                     help="steps of the Nakatsuji-Yasuda leg (FP64); 0 skips it")
     ap.add_argument("--spin-steps", type=int, default=5,
                     help="steps of the open-shell (N_alpha != N_beta) leg at r = 50 (FP64); 0 skips it")
+    ap.add_argument("--spin-ny-steps", type=int, default=2,
+                    help="steps of the open-shell leg with the NY 3-RDM at r = 50 (FP64); 0 skips it")
     ap.add_argument("--solve-eps", type=float, default=1e-5,
                     help="first step size of the acse_solve leg (the synthetic r = 50 integrals are "
                          "large: eps = 1e-3 raises ||R|| at the first trial)")
@@ -357,13 +359,15 @@ def spin_map_flops(r):
     return 13 * 2.0 * r ** 6 + 4 * 2.0 * lt * r * r * lt
 
 
-def bench_spin(acse, ctx, gen, torch, steps, warmup, eps, mode="fp64", name="r50s"):
+def bench_spin(acse, ctx, gen, torch, steps, warmup, eps, mode="fp64", name="r50s", ny=False):
     """One acse_step_spin per step on the open-shell workload (r = 50,
     N_alpha = 16, N_beta = 14): the residual, the update map, the per-block
     Euler step with trace restoration, the 1-RDMs per spin and the energy,
     with the block products in FP64 or as int8 exact-accumulation products
     ("int8crt").  Inputs restored from a pristine device copy inside the timed
-    region.  Checked against the stored FP64 oracle values of the same step."""
+    region.  Checked against the stored FP64 oracle values of the same step
+    (Valdemoro).  With ``ny`` both maps add the NY share (default open-shell
+    occupations), FP64 over spin-orbital tensors (2r = 100)."""
     dev = torch.device("cuda", 0)
     p = gen.named_spin(name)
     r = p["r"]
@@ -374,7 +378,7 @@ def bench_spin(acse, ctx, gen, torch, steps, warmup, eps, mode="fp64", name="r50
     work = [t.clone() for t in pristine]
     prob = acse.ProblemSpin(r, p["Na"], p["Nb"], h.data_ptr(), V.data_ptr(), *[t.data_ptr() for t in work])
     outs = [torch.empty((r, r, r, r), dtype=torch.float64, device=dev) for _ in range(6)]
-    opts = acse.Context.options(mode)
+    opts = acse.Context.options(mode, sigma=True if ny else None)
     stream = ctx.stream
 
     def restore():
@@ -412,7 +416,7 @@ def bench_spin(acse, ctx, gen, torch, steps, warmup, eps, mode="fp64", name="r50
     restore()
     E1, n2 = ctx.step_spin_raw(prob, eps, opts, outs)
     err = None
-    if os.path.exists(SPIN_GOLDEN):
+    if os.path.exists(SPIN_GOLDEN) and not ny:
         g = json.load(open(SPIN_GOLDEN))
         idx = [tuple(t) for t in g["index"]]
         got = dict(zip(("R_aa", "R_bb", "R_ab", "U_aa", "U_bb", "U_ab"), [o.cpu().numpy() for o in outs]))
@@ -432,9 +436,21 @@ def bench_spin(acse, ctx, gen, torch, steps, warmup, eps, mode="fp64", name="r50
     kernel = ("gemm_mod_kernel on the 17 spin-block products per map (13 moduli; HIP-event time of its "
               "launches)" if mode == "int8crt" else
               "gemm_nt_kernel<TrF64> on the 17 spin-block products per map (HIP-event time of their launches)")
+    extra = {}
+    if ny:
+        n = 2 * r
+        ny_flops = 2 * 6 * 2 * n ** 6          # two maps, six n^2 x n^2 x n^2 GEMMs each
+        ny_ms, _ = prof["ny_share"]
+        nyg_ms, _ = prof["ny_gemm"]
+        extra = dict(ny_share_ms_per_step=ny_ms / steps, ny_gemm_ms_per_step=nyg_ms / steps,
+                     ny_gemm_flops_per_step=ny_flops,
+                     ny_gemm_tflops=ny_flops / (nyg_ms / steps * 1e-3) / 1e12,
+                     ny_gemm_frac_fp64=ny_flops / (nyg_ms / steps * 1e-3) / 1e12 / PEAK_TFLOPS["fp64"])
     return dict(
         workload=f"{name}: r={r}, N_alpha={p['Na']}, N_beta={p['Nb']}, three 2-RDM spin blocks, one "
-                 f"acse_step_spin (eps={eps}) per step, products {mode}",
+                 f"acse_step_spin (eps={eps}) per step, products {mode}"
+                 + (", NY 3-RDM (open-shell occupations)" if ny else ""),
+        **extra,
         ms_per_step=ms, steps_per_s=1e3 / ms, residual_ms=res_ms, residual_evals_per_s=1e3 / res_ms,
         stage_ms_per_step={k: v[0] / steps for k, v in prof.items()},
         block_gemm_flops_per_step=flops, useful_tflops_step=flops / (ms * 1e-3) / 1e12,
@@ -670,6 +686,9 @@ def main():
     if args.spin_steps > 0:
         line["non_singlet"] = {m: bench_spin(acse, ctx, gen, torch, args.spin_steps, min(args.warmup, 2), args.eps, m)
                                for m in ("int8crt", "fp64")}
+        if args.spin_ny_steps > 0:
+            line["non_singlet"]["ny_fp64"] = bench_spin(acse, ctx, gen, torch, args.spin_ny_steps, 1, args.eps,
+                                                        "fp64", ny=True)
         if args.solve_controls:
             line["non_singlet"]["solve_fp64"] = bench_solve_spin(
                 acse, ctx, gen, torch, args.solve_controls.split(","), args.solve_iters, args.solve_eps,

@@ -131,8 +131,10 @@ typedef struct {
                              are an ACSE_ERR_ARG */
   const int8_t *ny_sigma; /* HOST [r] or NULL, ACSE_RECON_NY only: +1 for an orbital occupied
                              in the Hartree-Fock reference, -1 for an unoccupied one;
-                             NULL = orbitals 0 .. n_alpha-1 occupied.  Other values are an
-                             ACSE_ERR_ARG. */
+                             NULL = orbitals 0 .. n_alpha-1 occupied.  The _spin calls
+                             take HOST [2r], one per spin orbital, alpha orbitals first
+                             (NULL = alpha orbitals below n_alpha and beta orbitals below
+                             n_beta occupied).  Other values are an ACSE_ERR_ARG. */
   int32_t moduli;         /* ACSE_INT8CRT: number of moduli, 8..15 (0 = 13); more moduli
                              give more bits k per operand (k = 40 / 44 / 48 at
                              K = 2500 for 12 / 13 / 14) and one more int8 product
@@ -448,13 +450,20 @@ acse_status acse_residual_noalloc(void *hip_stream, const acse_problem *prob, co
  *              2D(pa qb|rb sa) = -d2ab[p,q,s,r].
  * The residual and update come in the same three blocks (R_aa, R_bb, R_ab with
  * R_ab = R(ia jb|ka lb)); ||R||^2 = ||R_aa||^2 + ||R_bb||^2 + 4 ||R_ab||^2 over
- * spin orbitals.  These calls run the spin-orbital map (Valdemoro 3-RDM) over
- * spatial spin blocks: 17 r^2 x r^2 x r^2 products per map, in FP64 or (with
- * precision ACSE_INT8CRT, moduli as for the singlet calls) as int8
- * exact-accumulation products of FP64 accuracy.  Options: precision ACSE_FP64
- * or ACSE_INT8CRT, Valdemoro only, ACSE_FLAG_GENERAL_KERNELS allowed
- * (ACSE_FLAG_CHECK_INPUTS and the other precisions are ACSE_ERR_UNSUPPORTED);
- * tile as for acse_residual (FP64).  The first call allocates a workspace for
+ * spin orbitals.  These calls run the spin-orbital map over spatial spin
+ * blocks: 17 r^2 x r^2 x r^2 products per map, in FP64 or (with precision
+ * ACSE_INT8CRT, moduli as for the singlet calls) as int8 exact-accumulation
+ * products of FP64 accuracy.  Options: precision ACSE_FP64 or ACSE_INT8CRT,
+ * ACSE_FLAG_GENERAL_KERNELS allowed (ACSE_FLAG_CHECK_INPUTS and the other
+ * precisions are ACSE_ERR_UNSUPPORTED); tile as for acse_residual (FP64);
+ * either reconstruction.  With ACSE_RECON_NY (r <= 64, otherwise
+ * ACSE_ERR_UNSUPPORTED) the NY 3-cumulant of Eq. (8) joins both maps of a
+ * step: its share runs in FP64 over spin-orbital tensors (n = 2r spin
+ * orbitals; six n^2 x n^2 x n^2 GEMMs per map, each eight times the flops of
+ * a spatial-block product), also under ACSE_INT8CRT; its first call
+ * allocates (6 n^4 + n^2 + n) doubles and two n^2-row operand buffers for its
+ * r (1.1 GB at r = 32), reallocated when a larger r comes and kept until
+ * acse_destroy.  The first call allocates a workspace for
  * r_max: 48 r_max^4 doubles and 25 GEMM operand buffers (about 3.7 GB at
  * r_max = 50), kept until acse_destroy; the first ACSE_INT8CRT call adds the
  * residues of those buffers and of one launch's products (about 3.0 GB at

@@ -176,14 +176,15 @@ def euler(h, V, N, gamma, d2aa, d2ab, eps=1e-3, de_tol=1e-6, max_iter=100, contr
 
 
 def euler_spin(h, V, Na, Nb, ga, gb, d2aa, d2bb, d2ab, eps=1e-3, de_tol=1e-6, max_iter=100, control=FIXED,
-               max_halvings=8, active=None):
+               max_halvings=8, active=None, sigma_so=None):
     """The iteration of ``euler`` for a state of any S_z, on its three 2-RDM
     spin blocks (alpha-alpha, beta-beta, alpha-beta) and one 1-RDM per spin:
     the same stopping rules and the FIXED and BACKTRACK controls; each block is
     rescaled to its own trace before the step (a block of trace zero is set to
-    zero) and both 1-RDMs are contracted from the new 2-RDM.  Returns a dict
-    with ga, gb, d2aa, d2bb, d2ab of the returned state and the fields of
-    ``euler``."""
+    zero) and both 1-RDMs are contracted from the new 2-RDM.  ``sigma_so``
+    (2r reference occupations, alpha orbitals first) selects the NY 3-RDM of
+    Eq. (8) in both maps; None is Valdemoro.  Returns a dict with ga, gb,
+    d2aa, d2bb, d2ab of the returned state and the fields of ``euler``."""
     if control not in (FIXED, BACKTRACK):
         raise ValueError("the spin-block iteration takes the FIXED or BACKTRACK control")
     h = np.asarray(h, dtype=np.float64)
@@ -199,7 +200,7 @@ def euler_spin(h, V, Na, Nb, ga, gb, d2aa, d2bb, d2ab, eps=1e-3, de_tol=1e-6, ma
 
     def residual(ga, gb, blocks):
         d1, d2 = rdm.spin_blocks_to_spin_orbital(ga, gb, *blocks)
-        R = residual_map(K, d1, d2, hermitian=True).numpy()
+        R = residual_map(K, d1, d2, hermitian=True, sigma_so=sigma_so).numpy()
         return R, float(np.sum(R ** 2)), d1, d2, float(np.sum(K * d2))
 
     R, f, d1, d2, E = residual(ga, gb, blocks)
@@ -207,7 +208,7 @@ def euler_spin(h, V, Na, Nb, ga, gb, d2aa, d2bb, d2ab, eps=1e-3, de_tol=1e-6, ma
     e = eps
     for n in range(max_iter):
         Rm = R if mask is None else R * mask
-        U = residual_map(Rm, d1, d2, hermitian=False).numpy()
+        U = residual_map(Rm, d1, d2, hermitian=False, sigma_so=sigma_so).numpy()
         ublocks = rdm.spin_orbital_to_spin_blocks(U)
         traces = tuple(float(np.einsum('pqpq->', b)) for b in blocks)
 

@@ -205,11 +205,15 @@ def _check_dev2(t, r, name, device):
         raise ValueError(f"{name} must hold r^2 = {r * r} elements (r = {r}), got shape {tuple(t.shape)}")
 
 
-def _check_opts(opts, r):
-    """The host arrays of the options (active mask, NY occupations) must cover r orbitals."""
+def _check_opts(opts, r, spin=False):
+    """The host arrays of the options must cover the problem: the active mask r
+    orbitals, the NY occupations r orbitals (2r spin orbitals, alpha first, for
+    the calls on states of any S_z)."""
     for name, n in getattr(opts, "_lens", {}).items():
-        if n is not None and n != r:
-            raise ValueError(f"options.{name} has {n} entries, the problem has r = {r} orbitals")
+        want = 2 * r if spin and name == "ny_sigma" else r
+        if n is not None and n != want:
+            what = f"2r = {want} spin orbitals" if want != r else f"r = {r} orbitals"
+            raise ValueError(f"options.{name} has {n} entries, the problem has {what}")
 
 
 class Context:
@@ -279,7 +283,9 @@ class Context:
     def options(precision="fp64", active=None, tile=-1, flags=0, sigma=None, moduli=0):
         """acse_options.  ``sigma`` selects the Nakatsuji-Yasuda reconstruction:
         True for the default reference occupations (orbitals below n_alpha
-        occupied) or a per-orbital sequence of +1 / -1; None is Valdemoro.
+        occupied; for the _spin calls alpha orbitals below n_alpha and beta
+        orbitals below n_beta) or a sequence of +1 / -1 per orbital (per spin
+        orbital, alpha first, for the _spin calls); None is Valdemoro.
         ``moduli``: modulus count of the "int8crt" precision (0 = 13)."""
         prec = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
         keep = None
@@ -471,7 +477,7 @@ class Context:
         return prob, t
 
     def residual_spin_raw(self, prob, opts, R_aa, R_bb, R_ab, want_norm=True):
-        _check_opts(opts, prob.r)
+        _check_opts(opts, prob.r, spin=True)
         for name, x in (("R_aa", R_aa), ("R_bb", R_bb), ("R_ab", R_ab)):
             _check_dev4(x, prob.r, name, self.device)
         n2 = ctypes.c_double(0.0)
@@ -480,17 +486,17 @@ class Context:
         return n2.value
 
     def residual_spin(self, h, V, d1a, d1b, d2aa, d2bb, d2ab, n_alpha, n_beta, tile=-1, flags=0,
-                      precision="fp64", moduli=0):
+                      precision="fp64", moduli=0, sigma=None):
         """R_aa, R_bb, R_ab (device) and ||R||^2 of Eq. (4) for a state of any S_z
-        (precision "fp64" or "int8crt")."""
+        (precision "fp64" or "int8crt"; ``sigma`` as for ``options``)."""
         prob, keep = self.problem_spin(h, V, d1a, d1b, d2aa, d2bb, d2ab, n_alpha, n_beta)
         r = prob.r
         R = [torch.empty((r, r, r, r), dtype=torch.float64, device=self.device) for _ in range(3)]
-        n2 = self.residual_spin_raw(prob, self.options(precision, None, tile, flags, moduli=moduli), *R)
+        n2 = self.residual_spin_raw(prob, self.options(precision, None, tile, flags, sigma, moduli), *R)
         return R[0], R[1], R[2], n2
 
     def step_spin_raw(self, prob, eps, opts, outs=(None,) * 6, want=True):
-        _check_opts(opts, prob.r)
+        _check_opts(opts, prob.r, spin=True)
         for name, x in zip(("R_aa", "R_bb", "R_ab", "U_aa", "U_bb", "U_ab"), outs):
             if x is not None:
                 _check_dev4(x, prob.r, name, self.device)
@@ -502,7 +508,7 @@ class Context:
         return e.value, n2.value
 
     def step_spin(self, h, V, d1a, d1b, d2aa, d2bb, d2ab, n_alpha, n_beta, eps=1e-3, active=None, tile=-1,
-                  return_ru=False, flags=0, precision="fp64", moduli=0):
+                  return_ru=False, flags=0, precision="fp64", moduli=0, sigma=None):
         """One Euler step of Eq. (9) for a state of any S_z on device copies; a dict
         with the new d1a, d1b, d2aa, d2bb, d2ab, the energy after the step and
         ||R||^2 before it (and R, U blocks with return_ru)."""
@@ -511,7 +517,7 @@ class Context:
         outs = [None] * 6
         if return_ru:
             outs = [torch.empty((r, r, r, r), dtype=torch.float64, device=self.device) for _ in range(6)]
-        E, n2 = self.step_spin_raw(prob, eps, self.options(precision, active, tile, flags, moduli=moduli), outs)
+        E, n2 = self.step_spin_raw(prob, eps, self.options(precision, active, tile, flags, sigma, moduli), outs)
         res = dict(d1a=t[2], d1b=t[3], d2aa=t[4], d2bb=t[5], d2ab=t[6], energy=E, norm2=n2)
         if return_ru:
             res.update(zip(("R_aa", "R_bb", "R_ab", "U_aa", "U_bb", "U_ab"), outs))
@@ -519,7 +525,7 @@ class Context:
 
     def solve_spin_raw(self, prob, opts, sopts, capacity=256):
         """acse_solve_spin on a prepared problem; returns (SolveResult, [Trial])."""
-        _check_opts(opts, prob.r)
+        _check_opts(opts, prob.r, spin=True)
         res = SolveResult()
         hist = (Trial * max(1, capacity))()
         self._check(_lib.acse_solve_spin(self._h, ctypes.byref(prob), ctypes.byref(opts), ctypes.byref(sopts),
@@ -528,7 +534,7 @@ class Context:
 
     def solve_spin(self, h, V, d1a, d1b, d2aa, d2bb, d2ab, n_alpha, n_beta, eps=1e-3, de_tol=1e-6,
                    max_iter=100, control="fixed", max_halvings=8, precision="fp64", active=None, tile=-1,
-                   flags=0, capacity=256, moduli=0):
+                   flags=0, capacity=256, moduli=0, sigma=None):
         """The Euler iteration of ``solve`` for a state of any S_z on device
         copies of the inputs (acse_solve_spin; controls "fixed" and
         "backtrack").  Returns a dict with the final d1a, d1b, d2aa, d2bb, d2ab
@@ -536,7 +542,7 @@ class Context:
         prob, t = self.problem_spin(h, V, d1a, d1b, d2aa, d2bb, d2ab, n_alpha, n_beta)
         so = SolveOptions(float(eps), float(de_tol), 0.0, int(max_iter),
                           CONTROLS[control] if isinstance(control, str) else int(control), int(max_halvings), 0)
-        res, hist = self.solve_spin_raw(prob, self.options(precision, active, tile, flags, moduli=moduli), so,
+        res, hist = self.solve_spin_raw(prob, self.options(precision, active, tile, flags, sigma, moduli), so,
                                         capacity)
         return dict(d1a=t[2], d1b=t[3], d2aa=t[4], d2bb=t[5], d2ab=t[6], energy0=res.energy0,
                     norm2_0=res.norm2_0, energy=res.energy, norm2=res.norm2, eps=res.eps,

@@ -2642,6 +2642,7 @@ extern "C" acse_status acse_autotune_batched(acse_ctx ctx, int32_t count, const 
 namespace {
 
 constexpr int kSpinNat = 50;   // natural r^4 arrays
+constexpr int kSpinNyMaxR = 64;  // the NY share's operand relayout stages n = 2r rows of n + 1 doubles in LDS
 constexpr int kSpinOps = 25;   // GEMM operand buffers
 enum { B0000 = 0, B0101 = 5, B0110 = 6, B1001 = 9, B1010 = 10, B1111 = 15 };
 constexpr int kSix[6] = {B0000, B1111, B0101, B1010, B0110, B1001};
@@ -2666,6 +2667,15 @@ struct SpinWs {
   // (allocated by the first acse_solve_spin call)
   void *kbase = nullptr;
   double *Nk[3] = {}, *gk[2] = {};
+  // the NY share over spin-orbital tensors (n = 2r spin orbitals): X, the
+  // 2-cumulant and its sigma-weighted copy, two intermediates, B, the two
+  // GEMM operands, Y and sigma (allocated by the first NY call for its r,
+  // grown when a larger r comes)
+  void *nybase = nullptr;
+  int ny_n = 0;
+  double *soX = nullptr, *soC2 = nullptr, *soCS = nullptr, *soW = nullptr, *soT = nullptr, *soB = nullptr;
+  double *soOpA = nullptr, *soOpB = nullptr, *soY = nullptr, *soSig = nullptr;
+  std::vector<double> so_sig;  // what soSig holds
 };
 
 acse_status ensure_spin_ws(acse_ctx c, SpinWs *&out) {
@@ -2743,8 +2753,17 @@ acse_status validate_spin(acse_ctx c, const acse_problem_spin *p, const acse_opt
     if (o->moduli != 0 && (o->moduli < kMinModuli || o->moduli > kMaxModuli))
       return fail(c, ACSE_ERR_ARG, "moduli must be 0 or in [" + std::to_string(kMinModuli) + ", " +
                                        std::to_string(kMaxModuli) + "]");
-    if (o->reconstruction != ACSE_RECON_V)
-      return fail(c, ACSE_ERR_UNSUPPORTED, "the spin-block path takes the Valdemoro reconstruction only");
+    if (o->reconstruction != ACSE_RECON_V && o->reconstruction != ACSE_RECON_NY)
+      return fail(c, ACSE_ERR_ARG, "unknown reconstruction");
+    if (o->reconstruction == ACSE_RECON_NY) {
+      if (p->r > kSpinNyMaxR)
+        return fail(c, ACSE_ERR_UNSUPPORTED, "the NY share of the spin-block path runs up to r = " +
+                                                 std::to_string(kSpinNyMaxR));
+      if (o->ny_sigma)
+        for (int q = 0; q < 2 * p->r; ++q)
+          if (o->ny_sigma[q] != 1 && o->ny_sigma[q] != -1)
+            return fail(c, ACSE_ERR_ARG, "ny_sigma entries must be +1 or -1");
+    }
     if (o->flags & ~ACSE_FLAG_GENERAL_KERNELS)
       return fail(c, (o->flags & ~(ACSE_FLAG_GENERAL_KERNELS | ACSE_FLAG_CHECK_INPUTS |
                                    ACSE_FLAG_BATCH_PERSISTENT)) ? ACSE_ERR_ARG
@@ -2753,8 +2772,15 @@ acse_status validate_spin(acse_ctx c, const acse_problem_spin *p, const acse_opt
     if (o->tile < -1 || o->tile >= gemm_num_tiles(GEMM_F64)) return fail(c, ACSE_ERR_ARG, "tile configuration out of range");
   }
   c->general = o && (o->flags & ACSE_FLAG_GENERAL_KERNELS);
-  c->ny_on = false;
   c->crt_moduli = (o && o->precision == ACSE_INT8CRT) ? (o->moduli ? o->moduli : kDefaultModuli) : 0;
+  // spin-orbital reference occupations, alpha orbitals first
+  c->ny_on = o && o->reconstruction == ACSE_RECON_NY;
+  if (c->ny_on) {
+    const int r = p->r;
+    c->ny_sigma.assign(2 * r, -1.0);
+    for (int q = 0; q < 2 * r; ++q)
+      c->ny_sigma[q] = o->ny_sigma ? (double)o->ny_sigma[q] : (q % r < (q < r ? p->n_alpha : p->n_beta) ? 1.0 : -1.0);
+  }
   return ACSE_OK;
 }
 
@@ -2954,11 +2980,172 @@ acse_status spin_xa_from_blocks(acse_ctx c, SpinWs &w, int r, const double *Xaa,
   return ACSE_OK;
 }
 
+// Workspace of the spin-block NY share for n spin orbitals (kept; grown when
+// a larger n comes, after the stream has drained).
+acse_status ensure_spin_ny(acse_ctx c, SpinWs &w, int n) {
+  if (w.nybase && w.ny_n >= n) return ACSE_OK;
+  if (w.nybase) {
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    (void)hipFree(w.nybase);
+    w.nybase = nullptr;
+    w.ny_n = 0;
+  }
+  const int64_t n2 = (int64_t)n * n;
+  const int64_t nat = round_up(n2 * n2 * 8, 256), opb = round_up(op_rows(n) * op_ld(n) * 8, 256);
+  const int64_t bytes = 6 * nat + 2 * opb + round_up(n2 * 8, 256) + round_up((int64_t)n * 8, 256);
+  if (hipMalloc(&w.nybase, bytes) != hipSuccess) {
+    (void)hipGetLastError();
+    w.nybase = nullptr;
+    return fail(c, ACSE_ERR_NOMEM, "cannot allocate the NY workspace of the spin-block path (" +
+                                       std::to_string(bytes) + " bytes)");
+  }
+  char *q = static_cast<char *>(w.nybase);
+  auto take = [&](int64_t b) { double *x = reinterpret_cast<double *>(q); q += b; return x; };
+  w.soX = take(nat); w.soC2 = take(nat); w.soCS = take(nat); w.soW = take(nat); w.soT = take(nat);
+  w.soB = take(nat);
+  w.soOpA = take(opb); w.soOpB = take(opb);
+  w.soY = take(round_up(n2 * 8, 256));
+  w.soSig = take(round_up((int64_t)n * 8, 256));
+  w.ny_n = n;
+  w.so_sig.clear();
+  return ACSE_OK;
+}
+
+// out[lo] = alpha sum A[la] B[lb] over natural n^4 arrays whose axes carry
+// the letters la, lb, lo (four distinct letters each): the two letters A and B
+// share and lo lacks are summed.  Both operands are relaid out as
+// [(two free letters)][(the two summed letters)], then one FP64 GEMM writes
+// through 4-index store strides.
+acse_status so_contract(acse_ctx c, SpinWs &w, int n, double *out, const char *lo, const double *A, const char *la,
+                        const double *B, const char *lb, double alpha) {
+  auto pos = [](const char *t, char ch) {
+    for (int k = 0; k < 4; ++k)
+      if (t[k] == ch) return k;
+    return -1;
+  };
+  const int64_t n2 = (int64_t)n * n;
+  const int64_t pw[4] = {n2 * n, n2, n, 1};
+  char fa[2], fb[2], kc[2];
+  int nfa = 0, nfb = 0, nk = 0;
+  for (int k = 0; k < 4; ++k) {
+    const char ch = lo[k];
+    const bool ia = pos(la, ch) >= 0, ib = pos(lb, ch) >= 0;
+    if (ia == ib || (ia ? nfa : nfb) == 2) return fail(c, ACSE_ERR_HIP, "internal: bad spin-orbital contraction");
+    (ia ? fa[nfa++] : fb[nfb++]) = ch;
+  }
+  for (int k = 0; k < 4; ++k) {
+    const char ch = la[k];
+    if (pos(lo, ch) >= 0) continue;
+    if (pos(lb, ch) < 0 || nk == 2) return fail(c, ACSE_ERR_HIP, "internal: bad spin-orbital contraction");
+    kc[nk++] = ch;
+  }
+  if (nfa != 2 || nfb != 2 || nk != 2) return fail(c, ACSE_ERR_HIP, "internal: bad spin-orbital contraction");
+  hipStream_t s = c->stream;
+  const int64_t rows = op_rows(n), ld = op_ld(n);
+  auto relayout = [&](const double *src, const char *ls, const char *f, double *dst) {
+    PermArgs a{};
+    a.r = n; a.rows = rows; a.ld = ld; a.src1 = src; a.c1 = 1.0;
+    const char order[4] = {f[0], f[1], kc[0], kc[1]};
+    for (int k = 0; k < 4; ++k) a.s1[k] = pw[pos(ls, order[k])];
+    return launch_permute4(GEMM_F64, a, OperandRef{dst, nullptr}, s);
+  };
+  HIP_TRY(c, relayout(A, la, fa, w.soOpA));
+  HIP_TRY(c, relayout(B, lb, fb, w.soOpB));
+  GemmBatch b{};
+  b.count = 1;
+  GemmProb &P = b.p[0];
+  P.A = w.soOpA; P.B = w.soOpB; P.C = out; P.alpha = alpha;
+  P.M = (int)n2; P.N = (int)n2; P.ld = (int)ld; P.Kp = gemm_kp(GEMM_F64, (int)n2, (int)ld); P.rdiv = n;
+  P.sm1 = pw[pos(lo, fa[0])]; P.sm0 = pw[pos(lo, fa[1])]; P.sn1 = pw[pos(lo, fb[0])]; P.sn0 = pw[pos(lo, fb[1])];
+  P.ksplit = 1; P.kchunk = P.Kp; P.accumulate = 0;
+  StageTimer t7(c, 7);  // the products alone
+  HIP_TRY(c, gemm_launch(GEMM_F64, gemm_default_cfg(GEMM_F64, (int)n2, (int)n2), b, s));
+  return ACSE_OK;
+}
+
+// The NY share of the spin-block map: S_b -= C_b for the three output blocks,
+// C = B - B(k<->l), B the contraction of X with the NY 3-cumulant of Eq. (8)
+// (App. D), in FP64 over spin-orbital tensors (n = 2r).  The 36 signed
+// permutations of the cumulant product collapse by the pair antisymmetry of
+// the 2-cumulant and of X's lower pair into
+//   B = 4 [sw(t_il) + t_pl - 2 sw(t_ir) - 2 t_pr],  sw(t) = t - t(i<->j),
+//   t_il = sum X^{kp}_{rq} c^{ia}_{rq} cs^{jp}_{al},   t_pl = sum Y_ka cs^{ij}_{al},
+//   Y_ka = sum X^{kp}_{rq} c^{pa}_{rq},
+//   t_ir = sum X^{kp}_{rq} cs^{jp}_{ar} c^{ia}_{lq},   t_pr = sum X^{kp}_{rq} c^{pa}_{lq} cs^{ij}_{ar},
+// with c the 2-cumulant and cs = c with its first lower index a weighted by
+// sigma_a; each t is two pairwise contractions (n^6 each).  X is the map's
+// operator, antisymmetric in both pairs (the X_A blocks).
+acse_status ny_spin_share(acse_ctx c, SpinWs &w, const acse_problem_spin *p, const double *ga, const double *gb) {
+  const int r = p->r, n = 2 * r;
+  const int64_t n2 = (int64_t)n * n, n3 = n2 * n;
+  hipStream_t s = c->stream;
+  StageTimer t6(c, 6);
+  acse_status st = ensure_spin_ny(c, w, n);
+  if (st != ACSE_OK) return st;
+  if (w.so_sig != c->ny_sigma) {
+    // the host copy stays in the workspace until the next change, after a synchronisation
+    HIP_TRY(c, hipStreamSynchronize(s));
+    w.so_sig = c->ny_sigma;
+    HIP_TRY(c, hipMemcpyAsync(w.soSig, w.so_sig.data(), (size_t)n * sizeof(double), hipMemcpyHostToDevice, s));
+  }
+  HIP_TRY(c, launch_fill(n2 * n2, 0.0, w.soX, s));
+  for (int b : kSix) HIP_TRY(c, launch_so_embed(r, b, w.XA[b], 1.0, w.soX, s));
+  HIP_TRY(c, launch_so_cumulant(r, ga, gb, p->d2aa, p->d2bb, p->d2ab, w.soSig, w.soC2, w.soCS, s));
+  auto t4 = [](const double *in, double cf, int64_t s0, int64_t s1, int64_t s2, int64_t s3) {
+    Term4 t{};
+    t.in = in; t.c = cf; t.s[0] = s0; t.s[1] = s1; t.s[2] = s2; t.s[3] = s3;
+    return t;
+  };
+  // x = i, y = l; then the p, l term through Y
+  if ((st = so_contract(c, w, n, w.soW, "kpia", w.soX, "kprq", w.soC2, "iarq", 1.0)) != ACSE_OK) return st;
+  HIP_TRY(c, launch_so_trace_y(n, w.soW, w.soY, s));
+  if ((st = so_contract(c, w, n, w.soT, "ijkl", w.soW, "kpia", w.soCS, "jpal", 1.0)) != ACSE_OK) return st;
+  {
+    Terms4 T{};
+    T.n = 2;
+    T.t[0] = t4(w.soT, 4.0, n3, n2, n, 1);
+    T.t[1] = t4(w.soT, -4.0, n2, n3, n, 1);
+    HIP_TRY(c, launch_combine4(n, T, w.soB, 0, nullptr, s));
+  }
+  HIP_TRY(c, launch_so_tpl(n, 4.0, w.soY, w.soCS, w.soB, s));
+  // x = i, y = r (the y = q products equal these)
+  if ((st = so_contract(c, w, n, w.soW, "kqja", w.soX, "kprq", w.soCS, "jpar", 1.0)) != ACSE_OK) return st;
+  if ((st = so_contract(c, w, n, w.soT, "ijkl", w.soW, "kqja", w.soC2, "ialq", 1.0)) != ACSE_OK) return st;
+  {
+    Terms4 T{};
+    T.n = 2;
+    T.t[0] = t4(w.soT, -8.0, n3, n2, n, 1);
+    T.t[1] = t4(w.soT, 8.0, n2, n3, n, 1);
+    HIP_TRY(c, launch_combine4(n, T, w.soB, 1, nullptr, s));
+  }
+  // x = p, y = r
+  if ((st = so_contract(c, w, n, w.soW, "kral", w.soX, "kprq", w.soC2, "palq", 1.0)) != ACSE_OK) return st;
+  if ((st = so_contract(c, w, n, w.soT, "ijkl", w.soW, "kral", w.soCS, "ijar", 1.0)) != ACSE_OK) return st;
+  {
+    Terms4 T{};
+    T.n = 1;
+    T.t[0] = t4(w.soT, -8.0, n3, n2, n, 1);
+    HIP_TRY(c, launch_combine4(n, T, w.soB, 1, nullptr, s));
+  }
+  // S_b -= B_b - B_b(k<->l) on the spin block b of B
+  for (int b : {B0000, B1111, B0101}) {
+    const int64_t o0 = ((b >> 3) & 1) * (int64_t)r * n3, o1 = ((b >> 2) & 1) * (int64_t)r * n2;
+    const int64_t o2 = ((b >> 1) & 1) * (int64_t)r, o3 = (b & 1) * (int64_t)r;
+    Terms4 T{};
+    T.n = 2;
+    T.t[0] = t4(w.soB + o0 + o1 + o2 * n + o3, -1.0, n3, n2, n, 1);
+    T.t[1] = t4(w.soB + o0 + o1 + o3 * n + o2, 1.0, n3, n2, 1, n);
+    HIP_TRY(c, launch_combine4(r, T, w.S[b], 1, nullptr, s));
+  }
+  return ACSE_OK;
+}
+
 // F(X) for the X_A blocks in the workspace into O[0..2] = (aa, bb, ab);
 // sigma = -1 Hermitian X, +1 anti-Hermitian.  If Rm is not null it receives
 // the masked copy.  The squared block norms land in w.scal[slot .. slot+2].
-acse_status spin_map(acse_ctx c, SpinWs &w, int r, const double *ga, const double *gb, double sigma,
-                     double *const *O, const ActiveBits *mask, double *const *Rm, int slot) {
+acse_status spin_map(acse_ctx c, SpinWs &w, const acse_problem_spin *p, const double *ga, const double *gb,
+                     double sigma, double *const *O, const ActiveBits *mask, double *const *Rm, int slot) {
+  const int r = p->r;
   const int64_t r2 = (int64_t)r * r, r3 = r2 * r;
   const int ld = (int)op_ld(r);
   hipStream_t s = c->stream;
@@ -3145,6 +3332,12 @@ acse_status spin_map(acse_ctx c, SpinWs &w, int r, const double *ga, const doubl
     T.t[6] = term4(w.E[x.bli], -1.0, r, 1, 0, 3, 2);
     HIP_TRY(c, launch_combine4(r, T, w.S[out_blocks[q]], 0, nullptr, s));
   }
+  t4.stop();
+  if (c->ny_on) {
+    acse_status st = ny_spin_share(c, w, p, ga, gb);
+    if (st != ACSE_OK) return st;
+  }
+  StageTimer t4b(c, 4);
   // F = S + sigma S^T, the masked copy, the block norms
   for (int q = 0; q < 3; ++q) {
     const int b = out_blocks[q];
@@ -3224,7 +3417,7 @@ extern "C" acse_status acse_residual_spin(acse_ctx ctx, const acse_problem_spin 
   }
   if ((st = spin_xa_from_fold(ctx, *w, r)) != ACSE_OK) return st;
   double *O[3] = {R_aa, R_bb, R_ab};
-  if ((st = spin_map(ctx, *w, r, prob->d1a, prob->d1b, -1.0, O, nullptr, nullptr, 0)) != ACSE_OK) return st;
+  if ((st = spin_map(ctx, *w, prob, prob->d1a, prob->d1b, -1.0, O, nullptr, nullptr, 0)) != ACSE_OK) return st;
   if (!norm2_host) return ACSE_OK;
   double n[3];
   if ((st = spin_fetch(ctx, *w, n, 3)) != ACSE_OK) return st;
@@ -3257,13 +3450,13 @@ extern "C" acse_status acse_step_spin(acse_ctx ctx, acse_problem_spin *prob, dou
   }
   if ((st = spin_xa_from_fold(ctx, *w, r)) != ACSE_OK) return st;
   // R = F(K), block norms -> scal[0..2], masked copy
-  if ((st = spin_map(ctx, *w, r, prob->d1a, prob->d1b, -1.0, R, masked ? &act : nullptr, masked ? w->Rm : nullptr,
+  if ((st = spin_map(ctx, *w, prob, prob->d1a, prob->d1b, -1.0, R, masked ? &act : nullptr, masked ? w->Rm : nullptr,
                      0)) != ACSE_OK)
     return st;
   // U = F(R_m) on the same 2-RDM
   const double *const *Xm = masked ? w->Rm : R;
   if ((st = spin_xa_from_blocks(ctx, *w, r, Xm[0], Xm[1], Xm[2])) != ACSE_OK) return st;
-  if ((st = spin_map(ctx, *w, r, prob->d1a, prob->d1b, 1.0, U, nullptr, nullptr, 3)) != ACSE_OK) return st;
+  if ((st = spin_map(ctx, *w, prob, prob->d1a, prob->d1b, 1.0, U, nullptr, nullptr, 3)) != ACSE_OK) return st;
   // 2D <- (2D + eps U) per block at its input trace; 1-RDM per spin; energy
   {
     StageTimer t5(ctx, 5);
@@ -3342,7 +3535,7 @@ extern "C" acse_status acse_solve_spin(acse_ctx ctx, acse_problem_spin *prob, co
     acse_status q;
     if ((q = spin_prep(ctx, w, prob)) != ACSE_OK) return q;
     if ((q = spin_xa_from_fold(ctx, w, r)) != ACSE_OK) return q;
-    if ((q = spin_map(ctx, w, r, prob->d1a, prob->d1b, -1.0, w.R, masked ? &act : nullptr,
+    if ((q = spin_map(ctx, w, prob, prob->d1a, prob->d1b, -1.0, w.R, masked ? &act : nullptr,
                       masked ? w.Rm : nullptr, 0)) != ACSE_OK)
       return q;
     ++res->maps;
@@ -3390,7 +3583,7 @@ extern "C" acse_status acse_solve_spin(acse_ctx ctx, acse_problem_spin *prob, co
     // U_n = F(R_m) on the operands of 2D_n (left in place by its residual)
     const double *const *Xm = masked ? w.Rm : w.R;
     if ((st = spin_xa_from_blocks(ctx, w, r, Xm[0], Xm[1], Xm[2])) != ACSE_OK) return st;
-    if ((st = spin_map(ctx, w, r, prob->d1a, prob->d1b, 1.0, w.U, nullptr, nullptr, 3)) != ACSE_OK) return st;
+    if ((st = spin_map(ctx, w, prob, prob->d1a, prob->d1b, 1.0, w.U, nullptr, nullptr, 3)) != ACSE_OK) return st;
     ++res->maps;
     // keep 2D_n and 1D_n; the block traces the trials restore
     for (int k = 0; k < 3; ++k) HIP_TRY(ctx, hipMemcpyAsync(w.Nk[k], d2[k], n4 * 8, hipMemcpyDeviceToDevice, s));
@@ -3444,6 +3637,7 @@ void release_spin_ws(acse_ctx c) {
   SpinWs *w = static_cast<SpinWs *>(c->spws);
   if (w && w->cbase) (void)hipFree(w->cbase);
   if (w && w->kbase) (void)hipFree(w->kbase);
+  if (w && w->nybase) (void)hipFree(w->nybase);
   delete w;
   c->spws = nullptr;
 }

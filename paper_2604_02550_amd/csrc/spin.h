@@ -53,4 +53,20 @@ hipError_t launch_unpack_rows_lt(int r, const double *C, int64_t ldc, double *ou
 hipError_t launch_spin_1rdm(int r, int N, const double *d2aa, const double *d2bb, const double *d2ab, double *ga,
                             double *gb, hipStream_t s);
 
+// ---- spin-orbital tensors of the NY share (n = 2r spin orbitals, alpha
+// orbitals first: spin orbital p + r sigma) ------------------------------------
+// Spin-block (bits b, bit 3 - t set when index t is beta) of a natural n^4
+// array: out[(i + r s0), (j + r s1), (k + r s2), (l + r s3)] = c in[i,j,k,l].
+hipError_t launch_so_embed(int r, int bits, const double *in, double c, double *out, hipStream_t s);
+// The spin-orbital 2-cumulant of a state given by its spin blocks,
+// c2[I,J,A,B] = 2D[I,J,A,B] - (1D[I,A] 1D[J,B] - 1D[J,A] 1D[I,B]) / 2 with 2D
+// lifted from (d2aa, d2bb, d2ab) by the pair antisymmetry and 1D
+// spin-diagonal (ga, gb), and cs = c2 with the third index scaled by sig[A].
+hipError_t launch_so_cumulant(int r, const double *ga, const double *gb, const double *d2aa, const double *d2bb,
+                              const double *d2ab, const double *sig, double *c2, double *cs, hipStream_t s);
+// Y[k,a] = sum_p W[k,p,p,a] (n x n from a natural n^4 array).
+hipError_t launch_so_trace_y(int n, const double *W, double *Y, hipStream_t s);
+// B[i,j,k,l] += c sum_a Y[k,a] cs[i,j,a,l].
+hipError_t launch_so_tpl(int n, double c, const double *Y, const double *cs, double *B, hipStream_t s);
+
 }  // namespace acse

@@ -141,6 +141,81 @@ k_unpack_rows_lt(int r, const double *__restrict__ C, int64_t ldc, double *__res
   out[e] = v;
 }
 
+// One thread per spatial element of the block; the writes of a thread run
+// along l (contiguous in the block of the output).
+__global__ void __launch_bounds__(256)
+k_so_embed(int r, int bits, const double *__restrict__ in, double c, double *__restrict__ out) {
+  const int64_t r2 = (int64_t)r * r;
+  const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (e >= r2 * r2) return;
+  const int l = (int)(e % r), k = (int)((e / r) % r), j = (int)((e / r2) % r), i = (int)(e / (r2 * r));
+  const int64_t n = 2 * (int64_t)r;
+  const int i2 = i + (((bits >> 3) & 1) ? r : 0), j2 = j + (((bits >> 2) & 1) ? r : 0);
+  const int k2 = k + (((bits >> 1) & 1) ? r : 0), l2 = l + ((bits & 1) ? r : 0);
+  out[((i2 * n + j2) * n + k2) * n + l2] = c * in[e];
+}
+
+// One thread per spin-orbital element (I,J,A,B).
+__global__ void __launch_bounds__(256)
+k_so_cumulant(int r, const double *__restrict__ ga, const double *__restrict__ gb, const double *__restrict__ d2aa,
+              const double *__restrict__ d2bb, const double *__restrict__ d2ab, const double *__restrict__ sig,
+              double *__restrict__ c2, double *__restrict__ cs) {
+  const int64_t n = 2 * (int64_t)r, n2 = n * n;
+  const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (e >= n2 * n2) return;
+  const int B = (int)(e % n), A = (int)((e / n) % n), J = (int)((e / n2) % n), I = (int)(e / (n2 * n));
+  const int si = I >= r, sj = J >= r, sa = A >= r, sb = B >= r;
+  const int i = I - si * r, j = J - sj * r, a = A - sa * r, b = B - sb * r;
+  const int64_t r2 = (int64_t)r * r;
+  auto at = [&](int p, int q, int u, int v) { return ((int64_t)p * r + q) * r2 + (int64_t)u * r + v; };
+  // 2D from the blocks: the fixed-spin blocks and the three mixed ones by the
+  // antisymmetry of each index pair; zero unless the spins of (I,J) are those of (A,B)
+  double d = 0.0;
+  const int code = (si << 3) | (sj << 2) | (sa << 1) | sb;
+  switch (code) {
+    case 0x0: d = d2aa[at(i, j, a, b)]; break;
+    case 0xF: d = d2bb[at(i, j, a, b)]; break;
+    case 0x5: d = d2ab[at(i, j, a, b)]; break;
+    case 0xA: d = d2ab[at(j, i, b, a)]; break;
+    case 0x6: d = -d2ab[at(i, j, b, a)]; break;
+    case 0x9: d = -d2ab[at(j, i, a, b)]; break;
+    default: break;
+  }
+  // 1D spin-diagonal
+  auto g1 = [&](int p, int sp, int q, int sq) -> double {
+    if (sp != sq) return 0.0;
+    return (sp ? gb : ga)[(int64_t)p * r + q];
+  };
+  const double v = d - 0.5 * (g1(i, si, a, sa) * g1(j, sj, b, sb) - g1(j, sj, a, sa) * g1(i, si, b, sb));
+  c2[e] = v;
+  cs[e] = sig[A] * v;
+}
+
+// One thread per (k,a): the sum over p in a fixed order.
+__global__ void __launch_bounds__(256) k_so_trace_y(int n, const double *__restrict__ W, double *__restrict__ Y) {
+  const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (e >= (int64_t)n * n) return;
+  const int k = (int)(e / n), a = (int)(e % n);
+  const int64_t n2 = (int64_t)n * n;
+  double acc = 0.0;
+  for (int p = 0; p < n; ++p) acc += W[((int64_t)k * n + p) * n2 + (int64_t)p * n + a];
+  Y[e] = acc;
+}
+
+// One thread per output element (i,j,k,l), the sum over a in a fixed order.
+__global__ void __launch_bounds__(256)
+k_so_tpl(int n, double c, const double *__restrict__ Y, const double *__restrict__ cs, double *__restrict__ B) {
+  const int64_t n2 = (int64_t)n * n;
+  const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (e >= n2 * n2) return;
+  const int l = (int)(e % n), k = (int)((e / n) % n);
+  const int64_t ij = e / n2;
+  const double *y = Y + (int64_t)k * n, *q = cs + ij * n2 + l;
+  double acc = 0.0;
+  for (int a = 0; a < n; ++a) acc += y[a] * q[(int64_t)a * n];
+  B[e] += c * acc;
+}
+
 inline dim3 grid1(int64_t n) { return dim3((unsigned)((n + 255) / 256)); }
 
 }  // namespace
@@ -187,6 +262,29 @@ hipError_t launch_spin_update(int r, double eps, double *const *d2, const double
 
 hipError_t launch_unpack_rows_lt(int r, const double *C, int64_t ldc, double *out, hipStream_t s) {
   hipLaunchKernelGGL(k_unpack_rows_lt, grid1((int64_t)r * r * r * r), dim3(256), 0, s, r, C, ldc, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_so_embed(int r, int bits, const double *in, double c, double *out, hipStream_t s) {
+  hipLaunchKernelGGL(k_so_embed, grid1((int64_t)r * r * r * r), dim3(256), 0, s, r, bits, in, c, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_so_cumulant(int r, const double *ga, const double *gb, const double *d2aa, const double *d2bb,
+                              const double *d2ab, const double *sig, double *c2, double *cs, hipStream_t s) {
+  const int64_t n = 2 * (int64_t)r;
+  hipLaunchKernelGGL(k_so_cumulant, grid1(n * n * n * n), dim3(256), 0, s, r, ga, gb, d2aa, d2bb, d2ab, sig, c2,
+                     cs);
+  return hipGetLastError();
+}
+
+hipError_t launch_so_trace_y(int n, const double *W, double *Y, hipStream_t s) {
+  hipLaunchKernelGGL(k_so_trace_y, grid1((int64_t)n * n), dim3(256), 0, s, n, W, Y);
+  return hipGetLastError();
+}
+
+hipError_t launch_so_tpl(int n, double c, const double *Y, const double *cs, double *B, hipStream_t s) {
+  hipLaunchKernelGGL(k_so_tpl, grid1((int64_t)n * n * n * n), dim3(256), 0, s, n, c, Y, cs, B);
   return hipGetLastError();
 }
 

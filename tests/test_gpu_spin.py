@@ -170,8 +170,11 @@ def test_spin_step_identities_and_errors(acse, ctx):
         ctx.residual_spin_raw(prob, ctx.options("fp32"), *R)
     with pytest.raises(acse.AcseError, match="UNSUPPORTED"):
         ctx.residual_spin_raw(prob, ctx.options("bf16x3"), *R)
-    with pytest.raises(acse.AcseError, match="UNSUPPORTED"):
-        ctx.residual_spin_raw(prob, ctx.options(sigma=True), *R)
+    # NY occupations: one per spin orbital, each +1 or -1
+    with pytest.raises(acse.AcseError, match="ARG"):
+        ctx.residual_spin_raw(prob, ctx.options(sigma=[1, 0] + [-1] * 30), *R)
+    with pytest.raises(ValueError, match="2r = 32 spin orbitals"):
+        ctx.residual_spin_raw(prob, ctx.options(sigma=[1] * 16), *R)
     singlet, _ = ctx.problem(p["h"], p["V"], p["gamma_a"], p["d2aa"], p["d2ab"], p["Na"], n_beta=p["Nb"])
     with pytest.raises(acse.AcseError, match="_spin calls"):
         ctx.residual_raw(singlet, ctx.options(), R[0], R[1])

@@ -184,9 +184,11 @@ def test_euler_spin_on_singlet_inputs_is_the_singlet_iteration():
             assert np.abs(g[k] - ref).max() < 1e-12 * max(1.0, np.abs(ref).max()), k
 
 
-def test_euler_spin_steps_are_step_spin_steps():
+@pytest.mark.parametrize("ny", [False, True])
+def test_euler_spin_steps_are_step_spin_steps(ny):
     """Every accepted fixed-eps step of the spin-block iteration is one
-    step_spin of the state before it (energy and blocks)."""
+    step_spin of the state before it (energy and blocks), with either 3-RDM
+    reconstruction."""
     from oracle import rdm
     from oracle import solve as sv
     from oracle import step as st
@@ -195,10 +197,12 @@ def test_euler_spin_steps_are_step_spin_steps():
     _, d2 = rdm.spin_blocks_to_spin_orbital(z, z, p["d2aa"], p["d2bb"], p["d2ab"])
     g = rdm.contract_to_1rdm(d2, 4)
     ga, gb = g[:5, :5].copy(), g[5:, 5:].copy()
+    sig = st.sigma_open_shell(5, 3, 1) if ny else None
     o = sv.euler_spin(p["h"], p["V"], 3, 1, ga, gb, p["d2aa"], p["d2bb"], p["d2ab"], eps=1e-2, de_tol=0.0,
-                      max_iter=2)
-    s1 = st.step_spin(p["h"], p["V"], 3, 1, ga, gb, p["d2aa"], p["d2bb"], p["d2ab"], 1e-2)
-    s2 = st.step_spin(p["h"], p["V"], 3, 1, s1["gamma_a"], s1["gamma_b"], s1["d2aa"], s1["d2bb"], s1["d2ab"], 1e-2)
+                      max_iter=2, sigma_so=sig)
+    s1 = st.step_spin(p["h"], p["V"], 3, 1, ga, gb, p["d2aa"], p["d2bb"], p["d2ab"], 1e-2, sigma_so=sig)
+    s2 = st.step_spin(p["h"], p["V"], 3, 1, s1["gamma_a"], s1["gamma_b"], s1["d2aa"], s1["d2bb"], s1["d2ab"], 1e-2,
+                      sigma_so=sig)
     assert o["iterations"] == 2 and [t[4] for t in o["trials"]] == [True, True]
     assert abs(o["trials"][0][1] - s1["energy"]) < 1e-12 * abs(s1["energy"])
     assert abs(o["energy"] - s2["energy"]) < 1e-12 * abs(s2["energy"])
