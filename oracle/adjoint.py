@@ -1,6 +1,7 @@
 """Adjoints of the residual and the energy (oracle; test infrastructure only).
 
-For a cotangent (Rbar_aa, Rbar_ab) on the residual blocks of Eq. (4), the
+For a cotangent (Rbar_aa, Rbar_ab) on the residual blocks of Eq. (4) (with
+the Valdemoro 3-RDM, or the NY one of Eq. (8) when occupations are given), the
 vector-Jacobian product is the gradient of
 
     L = <Rbar_aa, R_aa> + <Rbar_ab, R_ab>
@@ -110,12 +111,13 @@ def blocks_to_spin_orbital_t(gamma, d2aa, d2ab):
     return d1, d2
 
 
-def residual_blocks_t(h, V, N, gamma, d2aa, d2ab):
-    """(R_aa, R_ab) of Eq. (4) as a differentiable torch function."""
+def residual_blocks_t(h, V, N, gamma, d2aa, d2ab, sigma_so=None):
+    """(R_aa, R_ab) of Eq. (4) as a differentiable torch function; ``sigma_so``
+    (2r spin-orbital occupations) selects the NY 3-RDM."""
     r = h.shape[0]
     K = reduced_hamiltonian_t(h, V, N)
     d1, d2 = blocks_to_spin_orbital_t(gamma, d2aa, d2ab)
-    R = rs.residual_map(K, d1, d2, hermitian=True)
+    R = rs.residual_map(K, d1, d2, hermitian=True, sigma_so=sigma_so)
     return R[:r, :r, :r, :r], R[:r, r:, :r, r:]
 
 
@@ -129,11 +131,13 @@ def energy_t(h, V, N, d2aa, d2ab):
 
 # --- vector-Jacobian products --------------------------------------------------
 
-def residual_vjp(h, V, N, gamma, d2aa, d2ab, Rbar_aa, Rbar_ab):
+def residual_vjp(h, V, N, gamma, d2aa, d2ab, Rbar_aa, Rbar_ab, sigma=None):
     """Projected gradients of <Rbar, R> as numpy arrays:
-    dict(h, V, gamma, d2aa, d2ab)."""
+    dict(h, V, gamma, d2aa, d2ab).  ``sigma`` (per spatial orbital, +1 / -1,
+    the same for both spins) selects the NY 3-RDM; None is Valdemoro."""
     x = [_t(a).clone().requires_grad_(True) for a in (h, V, gamma, d2aa, d2ab)]
-    Raa, Rab = residual_blocks_t(x[0], x[1], N, x[2], x[3], x[4])
+    sso = None if sigma is None else np.concatenate([np.asarray(sigma, float)] * 2)
+    Raa, Rab = residual_blocks_t(x[0], x[1], N, x[2], x[3], x[4], sigma_so=sso)
     L = (_t(Rbar_aa) * Raa).sum() + (_t(Rbar_ab) * Rab).sum()
     g = torch.autograd.grad(L, x)
     proj = (proj_sym2, proj_V, proj_sym2, proj_aa, proj_ab)

@@ -61,11 +61,12 @@ def _trial(K, N, d2aa, d2ab, uaa, uab, eps):
     return a, b, gamma, float(np.sum(K * d2))
 
 
-def norm_slope(h, V, N, gamma, d2aa, d2ab, Raa, Rab, uaa, uab):
+def norm_slope(h, V, N, gamma, d2aa, d2ab, Raa, Rab, uaa, uab, sigma=None):
     """f'(0) for f(eps) = ||R(2D + eps U)||^2 over spin orbitals, from the
-    residual's vector-Jacobian product (cotangent 4 R_aa, 8 R_ab)."""
+    residual's vector-Jacobian product (cotangent 4 R_aa, 8 R_ab), with the
+    3-RDM ``sigma`` selects (None: Valdemoro, else NY)."""
     r = h.shape[0]
-    g = adjoint.residual_vjp(h, V, N, gamma, d2aa, d2ab, 4.0 * Raa, 8.0 * Rab)
+    g = adjoint.residual_vjp(h, V, N, gamma, d2aa, d2ab, 4.0 * Raa, 8.0 * Rab, sigma=sigma)
     _, u = rdm.blocks_to_spin_orbital(np.zeros((r, r)), uaa, uab)
     dgamma = rdm.contract_to_1rdm(u, N)[:r, :r]
     return float(np.sum(g["d2aa"] * uaa) + np.sum(g["d2ab"] * uab) + np.sum(g["gamma"] * dgamma))
@@ -93,11 +94,8 @@ def euler(h, V, N, gamma, d2aa, d2ab, eps=1e-3, de_tol=1e-6, max_iter=100, contr
     energies and norms of the input and returned states, the stop reason, the
     accepted-step count and the list of trials (eps, E, ||R||^2, step index,
     accepted).  ``sigma`` (per spatial orbital, +1 / -1) selects the NY
-    3-RDM of Eq. (8) for every map (not with the quadratic control, whose
-    slope is the Valdemoro adjoint)."""
+    3-RDM of Eq. (8) for every map and for the quadratic control's slope."""
     sso = None if sigma is None else rdm.sigma_spin_orbital(sigma)
-    if sso is not None and control == QUADRATIC:
-        raise ValueError("the quadratic control's slope is built for the Valdemoro 3-RDM")
     h = np.asarray(h, dtype=np.float64)
     V = np.asarray(V, dtype=np.float64)
     r = h.shape[0]
@@ -141,7 +139,7 @@ def euler(h, V, N, gamma, d2aa, d2ab, eps=1e-3, de_tol=1e-6, max_iter=100, contr
         chosen = t if ok(t["E"], t["f"]) else None
         cand = e
         if control == QUADRATIC:
-            g0 = norm_slope(h, V, N, gamma, d2aa, d2ab, raa, rab, uaa, uab)
+            g0 = norm_slope(h, V, N, gamma, d2aa, d2ab, raa, rab, uaa, uab, sigma=sigma)
             x = quadratic_trial_step(f, g0, e, t["f"], eps_max)
             if x is not None:
                 t2 = attempt(x)

@@ -36,9 +36,9 @@ PROBLEMS = {
 }
 
 
-def loss(p, Rb, **over):
+def loss(p, Rb, sigma=None, **over):
     q = {k: over.get(k, p[k]) for k in KEYS}
-    raa, rab, _ = ost.residual(q["h"], q["V"], p["N"], q["gamma"], q["d2aa"], q["d2ab"])
+    raa, rab, _ = ost.residual(q["h"], q["V"], p["N"], q["gamma"], q["d2aa"], q["d2ab"], sigma=sigma)
     return float(np.sum(Rb[0] * raa) + np.sum(Rb[1] * rab))
 
 
@@ -131,3 +131,29 @@ def test_planted_unprojected_gradient_breaks_symmetry():
     L = (torch.tensor(Rb[0]) * Raa).sum() + (torch.tensor(Rb[1]) * Rab).sum()
     raw = torch.autograd.grad(L, x)[4]
     assert float(torch.linalg.norm(raw - adj.proj_ab(raw))) > 1e-3 * float(torch.linalg.norm(raw))
+
+
+# occupations of the NY pins: not a prefix, so that the sigma weights matter
+NY_SIGMA = {"tiny_fci": [1, -1, 1, -1], "r5": [1, 1, -1, 1, -1]}
+
+
+@pytest.mark.parametrize("name", list(PROBLEMS))
+@pytest.mark.parametrize("key", KEYS)
+def test_residual_vjp_ny_finite_difference(name, key):
+    """The NY adjoint (autograd through the factorised NY share) against
+    central finite differences of the numpy NY forward."""
+    p = PROBLEMS[name]()
+    r = p["r"]
+    sig = NY_SIGMA[name]
+    rng = np.random.default_rng(13)
+    Rb = gen.cotangent(rng, r)
+    d = gen.symmetric_direction(rng, r)[key]
+    g = adj.residual_vjp(p["h"], p["V"], p["N"], p["gamma"], p["d2aa"], p["d2ab"], *Rb, sigma=sig)
+    t = 1e-5
+    fd = (loss(p, Rb, sig, **{key: p[key] + t * d}) - loss(p, Rb, sig, **{key: p[key] - t * d})) / (2 * t)
+    an = float(np.sum(g[key] * d))
+    scale = max(abs(an), np.linalg.norm(g[key]))
+    assert abs(fd - an) <= 1e-7 * scale, (fd, an)
+    # the NY share moves this gradient: the Valdemoro one differs
+    gv = adj.residual_vjp(p["h"], p["V"], p["N"], p["gamma"], p["d2aa"], p["d2ab"], *Rb)
+    assert np.linalg.norm(gv[key] - g[key]) > 1e-6 * np.linalg.norm(g[key])

@@ -64,6 +64,32 @@ def test_norm_slope_matches_finite_differences(name):
     assert abs(g_no_gamma - fd) > 1e-3 * abs(fd)
 
 
+@pytest.mark.parametrize("name", ["r4", "r6"])
+def test_norm_slope_ny_matches_finite_differences(name):
+    """The slope with the NY 3-RDM (its adjoint) against central differences
+    of the NY norm along the NY update direction."""
+    p = consistent(gen.problem(4, 4, 6, seed=7) if name == "r4" else gen.problem(6, 4, 12, seed=1))
+    r = p["r"]
+    sig = [1 if q % 3 != 2 else -1 for q in range(r)]
+    sso = rdm.sigma_spin_orbital(sig)
+    o = ost.step(p["h"], p["V"], p["N"], p["gamma"], p["d2aa"], p["d2ab"], 0.0, sigma=sig)
+    g0 = sv.norm_slope(p["h"], p["V"], p["N"], p["gamma"], p["d2aa"], p["d2ab"], o["R_aa"], o["R_ab"],
+                       o["U_aa"], o["U_ab"], sigma=sig)
+    K = rdm.reduced_hamiltonian(p["h"], p["V"], p["N"])
+
+    def f(x):
+        a, b, g1, _ = sv._trial(K, p["N"], p["d2aa"], p["d2ab"], o["U_aa"], o["U_ab"], x)
+        return sv._residual(K, g1, a, b, sso)[1]
+
+    h = 1e-6
+    fd = (f(h) - f(-h)) / (2 * h)
+    assert abs(g0 - fd) <= 1e-6 * abs(fd)
+    # the Valdemoro slope along the same direction is another number
+    gv = sv.norm_slope(p["h"], p["V"], p["N"], p["gamma"], p["d2aa"], p["d2ab"], o["R_aa"], o["R_ab"],
+                       o["U_aa"], o["U_ab"])
+    assert abs(gv - fd) > 1e-3 * abs(fd)
+
+
 def test_quadratic_trial_step():
     # f = 3 - 2x + 5x^2: minimiser 0.2
     f = lambda x: 3.0 - 2.0 * x + 5.0 * x * x
