@@ -167,10 +167,13 @@ def bench_batched(acse, ctx, gen, torch, modes, steps, warmup):
     return res
 
 
-def bench_vjp(acse, gen, torch, modes, steps, warmup):
+def bench_vjp(acse, gen, torch, modes, steps, warmup, ny_steps=2):
     """acse_residual_vjp with a seeded cotangent: on the differentiation workload
     (r = 30, N = 20) and on r = 50, N = 30, against the forward residual of the
-    same problem (one context per size)."""
+    same problem (one context per size).  With ny_steps > 0 also the NY
+    residual's adjoint ("ny_fp64": the FP64 Valdemoro adjoint plus the NY
+    share's, FP64 over spin-orbital tensors), ny_steps timed calls after one
+    warm-up, against the NY forward residual."""
     dev = torch.device("cuda", 0)
     res = {}
     for wl in ("vjp30", "r50"):
@@ -181,22 +184,25 @@ def bench_vjp(acse, gen, torch, modes, steps, warmup):
         Rb = [torch.as_tensor(a, device=dev).contiguous() for a in gen.cotangent(np.random.default_rng(5), r)]
         outs = [torch.empty_like(t) for t in keep]
         R = [torch.empty((r, r, r, r), dtype=torch.float64, device=dev) for _ in range(2)]
-        for mode in modes:
-            opts = acse.Context.options(mode)
-            ctx.autotune_raw(prob, opts)
+        for mode in list(modes) + (["ny_fp64"] if ny_steps > 0 else []):
+            ny = mode == "ny_fp64"
+            opts = acse.Context.options("fp64" if ny else mode, sigma=True if ny else None)
+            if not ny:
+                ctx.autotune_raw(prob, opts)
+            n_warm, n_steps = (1, ny_steps) if ny else (warmup, steps)
 
             def timed(fn):
-                for _ in range(warmup):
+                for _ in range(n_warm):
                     fn()
                 torch.cuda.synchronize()
                 a = torch.cuda.Event(enable_timing=True)
                 b = torch.cuda.Event(enable_timing=True)
                 a.record(ctx.stream)
-                for _ in range(steps):
+                for _ in range(n_steps):
                     fn()
                 b.record(ctx.stream)
                 torch.cuda.synchronize()
-                return a.elapsed_time(b) / steps
+                return a.elapsed_time(b) / n_steps
 
             ms_vjp = timed(lambda: ctx.residual_vjp_raw(prob, opts, Rb[0], Rb[1], *outs))
             ms_fwd = timed(lambda: ctx.residual_raw(prob, opts, R[0], R[1], want_norm=False))

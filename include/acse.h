@@ -157,8 +157,12 @@ typedef struct {
  *                  occupations from its n_alpha (ny_sigma must be NULL) and
  *                  the NY shares run in order on the context's stream.  The
  *                  adjoint (acse_residual_vjp) and the quadratic step control
- *                  of acse_solve (which needs it) are ACSE_ERR_UNSUPPORTED
- *                  with it. */
+ *                  of acse_solve (which needs it) take the NY share's adjoint
+ *                  for r <= 64 (ACSE_ERR_UNSUPPORTED above): FP64 over
+ *                  spin-orbital tensors (n = 2r; 15 n^2 x n^2 x n^2 GEMMs), its
+ *                  first call allocating (12 n^4 + 2 n^2 + n) doubles and two
+ *                  n^2-row operand buffers for its r (2.2 GB at r = 32),
+ *                  reallocated when a larger r comes, kept until acse_destroy. */
 typedef enum { ACSE_RECON_V = 0, ACSE_RECON_NY = 1 } acse_reconstruction;
 
 /* acse_options.flags: run the general-size kernels at every r (the one-index
@@ -255,7 +259,8 @@ acse_status acse_step(acse_ctx ctx, acse_problem *prob, double eps, const acse_o
  *                         unless within 5% of eps; the acceptable trial with the
  *                         smaller ||R||^2 is taken (the first on a tie), else
  *                         halving continues from the smaller step size.  Its
- *                         step size carries over.
+ *                         step size carries over.  With the NY reconstruction
+ *                         the slope is the NY residual's (r <= 64).
  * After an accepted step, |E_{n+1} - E_n| < de_tol ends the iteration.
  * Inputs whose 1D is not the contraction of 2D have it replaced by the
  * contraction at the first accepted step (as in acse_step).
@@ -330,8 +335,10 @@ acse_status acse_solve(acse_ctx ctx, acse_problem *prob, const acse_options *opt
  * accumulation of the gradients is FP64.  The first call allocates the
  * adjoint workspace (36 r_max^4 doubles plus 12 pair-index operand buffers),
  * the first ACSE_INT8CRT call the residues of those 12 buffers and of one
- * launch's products; both are kept until acse_destroy.  Errors as
- * acse_residual; the NY reconstruction is ACSE_ERR_UNSUPPORTED. */
+ * launch's products; both are kept until acse_destroy.  With the NY
+ * reconstruction (r <= 64, otherwise ACSE_ERR_UNSUPPORTED) the NY share's
+ * adjoint joins, in FP64 whatever the precision (see ACSE_RECON_NY).  Errors
+ * as acse_residual. */
 acse_status acse_residual_vjp(acse_ctx ctx, const acse_problem *prob, const acse_options *opts,
                               const double *Rbar_aa, const double *Rbar_ab, double *h_bar,
                               double *V_bar, double *d1_bar, double *d2aa_bar, double *d2ab_bar);

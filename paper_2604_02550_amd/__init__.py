@@ -571,16 +571,17 @@ class Context:
                                            _ptr(d1_bar), _ptr(d2aa_bar), _ptr(d2ab_bar)))
 
     def residual_vjp(self, h, V, d1, d2aa, d2ab, n_alpha, Rbar_aa, Rbar_ab, precision="fp64", tile=-1,
-                     flags=0):
+                     flags=0, sigma=None, moduli=0):
         """Cotangents (h, V, d1, d2aa, d2ab) of <Rbar, R> for the residual of Eq. (4),
-        projected onto the symmetry subspace of each input."""
+        projected onto the symmetry subspace of each input; ``sigma`` as for
+        ``options`` (the NY residual's adjoint)."""
         prob, keep = self.problem(h, V, d1, d2aa, d2ab, n_alpha)
         for name, x in (("Rbar_aa", Rbar_aa), ("Rbar_ab", Rbar_ab)):
             if _numel(x) != prob.r ** 4:
                 raise ValueError(f"{name} must hold r^4 = {prob.r ** 4} elements, got shape {_shape(x)}")
         rb = [_dev(x, self.device) for x in (Rbar_aa, Rbar_ab)]
         out = [torch.empty_like(x) for x in keep]
-        self.residual_vjp_raw(prob, self.options(precision, None, tile, flags), *rb, *out)
+        self.residual_vjp_raw(prob, self.options(precision, None, tile, flags, sigma, moduli), *rb, *out)
         return tuple(out)
 
     def residual_batched_raw(self, probs, opts, R_aa, R_ab, want_norm=True):
@@ -648,30 +649,30 @@ class Context:
 class ACSEResidual(torch.autograd.Function):
     """R = F(K) of Eq. (4) as an autograd function with the hand-written adjoint.
 
-    ``ACSEResidual.apply(ctx, h, V, d1, d2aa, d2ab, n_alpha, precision)`` returns
-    (R_aa, R_ab).  The gradients are those of the loss restricted to the
+    ``ACSEResidual.apply(ctx, h, V, d1, d2aa, d2ab, n_alpha, precision, sigma)``
+    returns (R_aa, R_ab); ``sigma`` (None: Valdemoro) as for ``Context.options``.  The gradients are those of the loss restricted to the
     symmetric inputs: each is projected onto its input's symmetry subspace
     (h, d1 symmetric; V with the 8-fold symmetry of (pq|rs); d2aa antisymmetric
     within each pair and Hermitian; d2ab Hermitian and pair-exchange symmetric).
     """
 
     @staticmethod
-    def forward(fctx, ctx, h, V, d1, d2aa, d2ab, n_alpha, precision="fp64"):
-        R_aa, R_ab, _ = ctx.residual(h, V, d1, d2aa, d2ab, n_alpha, precision)
-        fctx.acse = (ctx, n_alpha, precision)
+    def forward(fctx, ctx, h, V, d1, d2aa, d2ab, n_alpha, precision="fp64", sigma=None):
+        R_aa, R_ab, _ = ctx.residual(h, V, d1, d2aa, d2ab, n_alpha, precision, sigma=sigma)
+        fctx.acse = (ctx, n_alpha, precision, sigma)
         fctx.save_for_backward(h, V, d1, d2aa, d2ab)
         return R_aa, R_ab
 
     @staticmethod
     def backward(fctx, Rb_aa, Rb_ab):
-        ctx, n_alpha, precision = fctx.acse
+        ctx, n_alpha, precision, sigma = fctx.acse
         h, V, d1, d2aa, d2ab = fctx.saved_tensors
         r = h.shape[0]
         zero = torch.zeros((r, r, r, r), dtype=torch.float64, device=ctx.device)
         Rb_aa = zero if Rb_aa is None else Rb_aa
         Rb_ab = zero if Rb_ab is None else Rb_ab
-        g = ctx.residual_vjp(h, V, d1, d2aa, d2ab, n_alpha, Rb_aa, Rb_ab, precision)
-        return (None,) + tuple(x.to(t.dtype) for x, t in zip(g, (h, V, d1, d2aa, d2ab))) + (None, None)
+        g = ctx.residual_vjp(h, V, d1, d2aa, d2ab, n_alpha, Rb_aa, Rb_ab, precision, sigma=sigma)
+        return (None,) + tuple(x.to(t.dtype) for x, t in zip(g, (h, V, d1, d2aa, d2ab))) + (None, None, None)
 
 
 class ACSEEnergy(torch.autograd.Function):

@@ -34,6 +34,7 @@
 #include "gemm_crt.h"
 #include "ny.h"
 #include "ny_plan.h"
+#include "spin.h"
 #include "tensor_ops.h"
 #include "vjp.h"
 
@@ -144,6 +145,9 @@ struct acse_ctx_s {
   void *spbase = nullptr;
   int64_t spbytes = 0;
   void *spws = nullptr;    // its array table (a SpinWs)
+  // spin-orbital tensors of the NY share of the spin-block path and of the NY
+  // adjoint (an SoWs; allocated by the first such call for its r)
+  void *sows = nullptr;
 };
 
 namespace {
@@ -992,6 +996,7 @@ int keep_default(int best_cfg, double best_ms, int default_cfg, const double *ti
 
 const char *last_noctx_error();
 void release_spin_ws(acse_ctx c);
+void release_so_ws(acse_ctx c);
 
 acse_status fetch_scalars(acse_ctx c, double *norm2_host, double *E_host) {
   if (!norm2_host && !E_host) return ACSE_OK;
@@ -1104,6 +1109,7 @@ acse_status acse_destroy(acse_ctx ctx) {
   if (ctx->spbase) (void)hipFree(ctx->spbase);
   if (ctx->nycbase) (void)hipFree(ctx->nycbase);
   release_spin_ws(ctx);
+  release_so_ws(ctx);
   if (ctx->bbase) (void)hipFree(ctx->bbase);
   if (ctx->hdesc) (void)hipHostFree(ctx->hdesc);
   if (ctx->hdesc_done) (void)hipEventDestroy(ctx->hdesc_done);
@@ -1445,6 +1451,217 @@ struct Nat4 {
   }
 };
 
+// ---------------------------------------------------------------------------
+// Spin-orbital tensors (n = 2r spin orbitals, alpha first) for the NY share of
+// the spin-block map and for the NY adjoint: natural n^4 arrays, the two GEMM
+// operands of one pairwise contraction, two n^2 and one n-sized arrays.
+// Allocated by the first use for its n and array count, grown (after the
+// stream has drained) when a later call needs more, kept until acse_destroy.
+// ---------------------------------------------------------------------------
+constexpr int kSoMaxR = 64;      // the operand relayout stages n = 2r rows of n + 1 doubles in LDS
+constexpr int kSoMaxArrays = 12;
+struct SoWs {
+  void *base = nullptr;
+  int n = 0, narr = 0;
+  double *a[kSoMaxArrays] = {};
+  double *opA = nullptr, *opB = nullptr, *Y = nullptr, *Yb = nullptr, *sig = nullptr;
+  std::vector<double> sig_host;  // what sig holds
+};
+
+acse_status ensure_so_ws(acse_ctx c, int n, int narr, SoWs *&out) {
+  SoWs *w = static_cast<SoWs *>(c->sows);
+  if (!w) {
+    w = new (std::nothrow) SoWs();
+    if (!w) return fail(c, ACSE_ERR_NOMEM, "cannot allocate the spin-orbital workspace table");
+    c->sows = w;
+  }
+  out = w;
+  if (w->base && w->n >= n && w->narr >= narr) return ACSE_OK;
+  const int nn = std::max(n, w->n), na = std::max(narr, w->narr);
+  if (w->base) {
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    (void)hipFree(w->base);
+    w->base = nullptr;
+    w->n = w->narr = 0;
+  }
+  const int64_t n2 = (int64_t)nn * nn;
+  const int64_t nat = round_up(n2 * n2 * 8, 256), opb = round_up(op_rows(nn) * op_ld(nn) * 8, 256);
+  const int64_t sm = round_up(n2 * 8, 256);
+  const int64_t bytes = na * nat + 2 * opb + 2 * sm + round_up((int64_t)nn * 8, 256);
+  if (hipMalloc(&w->base, bytes) != hipSuccess) {
+    (void)hipGetLastError();
+    w->base = nullptr;
+    return fail(c, ACSE_ERR_NOMEM, "cannot allocate the spin-orbital workspace of the NY share (" +
+                                       std::to_string(bytes) + " bytes)");
+  }
+  char *q = static_cast<char *>(w->base);
+  auto take = [&](int64_t b) { double *x = reinterpret_cast<double *>(q); q += b; return x; };
+  for (int k = 0; k < na; ++k) w->a[k] = take(nat);
+  w->opA = take(opb);
+  w->opB = take(opb);
+  w->Y = take(sm);
+  w->Yb = take(sm);
+  w->sig = take(round_up((int64_t)nn * 8, 256));
+  w->n = nn;
+  w->narr = na;
+  w->sig_host.clear();
+  return ACSE_OK;
+}
+
+void release_so_ws(acse_ctx c) {
+  SoWs *w = static_cast<SoWs *>(c->sows);
+  if (w && w->base) (void)hipFree(w->base);
+  delete w;
+  c->sows = nullptr;
+}
+
+// The n spin-orbital occupations on the device (uploaded when they change;
+// the host copy stays in the workspace until the next change, after a
+// synchronisation).
+acse_status so_upload_sigma(acse_ctx c, SoWs &w, const std::vector<double> &sig) {
+  if (w.sig_host == sig) return ACSE_OK;
+  HIP_TRY(c, hipStreamSynchronize(c->stream));
+  w.sig_host = sig;
+  HIP_TRY(c, hipMemcpyAsync(w.sig, w.sig_host.data(), w.sig_host.size() * sizeof(double), hipMemcpyHostToDevice,
+                            c->stream));
+  return ACSE_OK;
+}
+
+// out[lo] (+)= alpha sum A[la] B[lb] over natural n^4 arrays whose axes carry
+// the letters la, lb, lo (four distinct letters each): the two letters A and B
+// share and lo lacks are summed.  Both operands are relaid out as
+// [(two free letters)][(the two summed letters)], then one FP64 GEMM writes
+// through 4-index store strides (accumulating if acc).
+acse_status so_contract(acse_ctx c, SoWs &w, int n, double *out, const char *lo, const double *A, const char *la,
+                        const double *B, const char *lb, double alpha, int acc = 0) {
+  auto pos = [](const char *t, char ch) {
+    for (int k = 0; k < 4; ++k)
+      if (t[k] == ch) return k;
+    return -1;
+  };
+  const int64_t n2 = (int64_t)n * n;
+  const int64_t pw[4] = {n2 * n, n2, n, 1};
+  char fa[2], fb[2], kc[2];
+  int nfa = 0, nfb = 0, nk = 0;
+  for (int k = 0; k < 4; ++k) {
+    const char ch = lo[k];
+    const bool ia = pos(la, ch) >= 0, ib = pos(lb, ch) >= 0;
+    if (ia == ib || (ia ? nfa : nfb) == 2) return fail(c, ACSE_ERR_HIP, "internal: bad spin-orbital contraction");
+    (ia ? fa[nfa++] : fb[nfb++]) = ch;
+  }
+  for (int k = 0; k < 4; ++k) {
+    const char ch = la[k];
+    if (pos(lo, ch) >= 0) continue;
+    if (pos(lb, ch) < 0 || nk == 2) return fail(c, ACSE_ERR_HIP, "internal: bad spin-orbital contraction");
+    kc[nk++] = ch;
+  }
+  if (nfa != 2 || nfb != 2 || nk != 2) return fail(c, ACSE_ERR_HIP, "internal: bad spin-orbital contraction");
+  hipStream_t s = c->stream;
+  const int64_t rows = op_rows(n), ld = op_ld(n);
+  auto relayout = [&](const double *src, const char *ls, const char *f, double *dst) {
+    PermArgs a{};
+    a.r = n; a.rows = rows; a.ld = ld; a.src1 = src; a.c1 = 1.0;
+    const char order[4] = {f[0], f[1], kc[0], kc[1]};
+    for (int k = 0; k < 4; ++k) a.s1[k] = pw[pos(ls, order[k])];
+    return launch_permute4(GEMM_F64, a, OperandRef{dst, nullptr}, s);
+  };
+  HIP_TRY(c, relayout(A, la, fa, w.opA));
+  HIP_TRY(c, relayout(B, lb, fb, w.opB));
+  GemmBatch b{};
+  b.count = 1;
+  GemmProb &P = b.p[0];
+  P.A = w.opA; P.B = w.opB; P.C = out; P.alpha = alpha;
+  P.M = (int)n2; P.N = (int)n2; P.ld = (int)ld; P.Kp = gemm_kp(GEMM_F64, (int)n2, (int)ld); P.rdiv = n;
+  P.sm1 = pw[pos(lo, fa[0])]; P.sm0 = pw[pos(lo, fa[1])]; P.sn1 = pw[pos(lo, fb[0])]; P.sn0 = pw[pos(lo, fb[1])];
+  P.ksplit = 1; P.kchunk = P.Kp; P.accumulate = acc;
+  StageTimer t7(c, 7);  // the products alone
+  HIP_TRY(c, gemm_launch(GEMM_F64, gemm_default_cfg(GEMM_F64, (int)n2, (int)n2), b, s));
+  return ACSE_OK;
+}
+
+Term4 so_term(const double *in, double cf, int64_t s0, int64_t s1, int64_t s2, int64_t s3) {
+  Term4 t{};
+  t.in = in; t.c = cf; t.s[0] = s0; t.s[1] = s1; t.s[2] = s2; t.s[3] = s3;
+  return t;
+}
+
+// The NY share's adjoint on the singlet residual (R = S - S^T, X = the fold's
+// X_A embedded as a spin-orbital tensor): the cotangent of B from
+// (Rbar_aa, Rbar_ab), then back through the pairwise contractions of B (the
+// forward intermediates recomputed), the trace Y, the sigma weighting and the
+// 2-cumulant to X, the 2-RDM and the 1-RDM, all FP64 over n = 2r spin
+// orbitals: 3 forward and 12 backward n^2 x n^2 x n^2 GEMMs.  The results are
+// added to the Valdemoro adjoint's accumulators: Abaa, Abab (gradients of the
+// fold's blocks), Gbaa, Gbab (half the gradients of d2aa, d2ab) and gbar (the
+// 1-RDM's), before their projections.
+acse_status ny_vjp_share_run(acse_ctx c, const acse_problem *p, const double *Aaa, const double *Aab,
+                             const double *Rbar_aa, const double *Rbar_ab, double *Abaa, double *Abab,
+                             double *Gbaa, double *Gbab, double *gbar) {
+  const int r = p->r, n = 2 * r;
+  const int64_t n2 = (int64_t)n * n, n3 = n2 * n;
+  hipStream_t s = c->stream;
+  StageTimer t6(c, 6);
+  SoWs *wp = nullptr;
+  acse_status st = ensure_so_ws(c, n, 12, wp);
+  if (st != ACSE_OK) return st;
+  SoWs &w = *wp;
+  double *X = w.a[0], *C2 = w.a[1], *CS = w.a[2], *W1 = w.a[3], *M2 = w.a[4], *M3 = w.a[5];
+  double *Bb = w.a[6], *Tb = w.a[7], *Wb = w.a[8], *Xb = w.a[9], *C2b = w.a[10], *CSb = w.a[11];
+  std::vector<double> sig(c->ny_sigma);  // both spins of an orbital share its occupation
+  sig.insert(sig.end(), c->ny_sigma.begin(), c->ny_sigma.end());
+  if ((st = so_upload_sigma(c, w, sig)) != ACSE_OK) return st;
+  // forward: X, the cumulants, the three first-stage intermediates, Y
+  HIP_TRY(c, launch_so_embed_singlet_x(r, Aaa, Aab, X, s));
+  HIP_TRY(c, launch_so_cumulant(r, p->d1, p->d1, p->d2aa, p->d2aa, p->d2ab, w.sig, C2, CS, s));
+  if ((st = so_contract(c, w, n, W1, "kpia", X, "kprq", C2, "iarq", 1.0)) != ACSE_OK) return st;
+  HIP_TRY(c, launch_so_trace_y(n, W1, w.Y, s));
+  if ((st = so_contract(c, w, n, M2, "kqja", X, "kprq", CS, "jpar", 1.0)) != ACSE_OK) return st;
+  if ((st = so_contract(c, w, n, M3, "kral", X, "kprq", C2, "palq", 1.0)) != ACSE_OK) return st;
+  // cotangent of B; Tb = sw(Bbar), the cotangent shape of the sw() terms
+  HIP_TRY(c, launch_so_bbar(r, Rbar_aa, Rbar_ab, 1.0, Bb, s));
+  {
+    Terms4 Q{};
+    Q.n = 2;
+    Q.t[0] = so_term(Bb, 1.0, n3, n2, n, 1);
+    Q.t[1] = so_term(Bb, -1.0, n2, n3, n, 1);
+    HIP_TRY(c, launch_combine4(n, Q, Tb, 0, nullptr, s));
+  }
+  // t_il (weight 4 on sw) and t_pl (weight 4, through Y)
+  if ((st = so_contract(c, w, n, Wb, "kpia", Tb, "ijkl", CS, "jpal", 4.0)) != ACSE_OK) return st;
+  HIP_TRY(c, launch_so_ybar(n, 4.0, Bb, CS, w.Yb, s));
+  HIP_TRY(c, launch_so_diag_add(n, w.Yb, Wb, s));
+  if ((st = so_contract(c, w, n, CSb, "jpal", Tb, "ijkl", W1, "kpia", 4.0)) != ACSE_OK) return st;
+  HIP_TRY(c, launch_so_csbar_pl(n, 4.0, Bb, w.Y, CSb, s));
+  if ((st = so_contract(c, w, n, Xb, "kprq", Wb, "kpia", C2, "iarq", 1.0)) != ACSE_OK) return st;
+  if ((st = so_contract(c, w, n, C2b, "iarq", Wb, "kpia", X, "kprq", 1.0)) != ACSE_OK) return st;
+  // t_ir (weight -8 on sw)
+  if ((st = so_contract(c, w, n, Wb, "kqja", Tb, "ijkl", C2, "ialq", -8.0)) != ACSE_OK) return st;
+  if ((st = so_contract(c, w, n, C2b, "ialq", Tb, "ijkl", M2, "kqja", -8.0, 1)) != ACSE_OK) return st;
+  if ((st = so_contract(c, w, n, Xb, "kprq", Wb, "kqja", CS, "jpar", 1.0, 1)) != ACSE_OK) return st;
+  if ((st = so_contract(c, w, n, CSb, "jpar", Wb, "kqja", X, "kprq", 1.0, 1)) != ACSE_OK) return st;
+  // t_pr (weight -8)
+  if ((st = so_contract(c, w, n, Wb, "kral", Bb, "ijkl", CS, "ijar", -8.0)) != ACSE_OK) return st;
+  if ((st = so_contract(c, w, n, CSb, "ijar", Bb, "ijkl", M3, "kral", -8.0, 1)) != ACSE_OK) return st;
+  if ((st = so_contract(c, w, n, Xb, "kprq", Wb, "kral", C2, "palq", 1.0, 1)) != ACSE_OK) return st;
+  if ((st = so_contract(c, w, n, C2b, "palq", Wb, "kral", X, "kprq", 1.0, 1)) != ACSE_OK) return st;
+  // cs = sigma_a c2, c2 = 2D - (1D^1D)/2, then the singlet lifts
+  HIP_TRY(c, launch_so_sigma_fold(n, w.sig, CSb, C2b, s));
+  HIP_TRY(c, launch_so_d1bar_singlet(r, p->d1, C2b, gbar, s));
+  HIP_TRY(c, launch_so_dbar_singlet(r, 0.5, C2b, Gbaa, Gbab, s));
+  HIP_TRY(c, launch_so_xbar_singlet(r, Xb, Abaa, Abab, s));
+  return ACSE_OK;
+}
+
+acse_status ny_vjp_share(acse_ctx c, const acse_problem *p, const double *Aaa, const double *Aab,
+                         const double *Rbar_aa, const double *Rbar_ab, double *Abaa, double *Abab, double *Gbaa,
+                         double *Gbab, double *gbar) {
+  try {
+    return ny_vjp_share_run(c, p, Aaa, Aab, Rbar_aa, Rbar_ab, Abaa, Abab, Gbaa, Gbab, gbar);
+  } catch (const std::exception &e) {
+    return fail(c, ACSE_ERR_NOMEM, std::string("NY adjoint: ") + e.what());
+  }
+}
+
 }  // namespace
 
 extern "C" acse_status acse_residual_vjp(acse_ctx ctx, const acse_problem *prob,
@@ -1453,7 +1670,8 @@ extern "C" acse_status acse_residual_vjp(acse_ctx ctx, const acse_problem *prob,
                                          double *d1_bar, double *d2aa_bar, double *d2ab_bar) {
   acse_status st = validate(ctx, prob, opts);
   if (st != ACSE_OK) return st;
-  if (ctx->ny_on) return fail(ctx, ACSE_ERR_UNSUPPORTED, "the adjoint is built for the Valdemoro reconstruction only");
+  if (ctx->ny_on && prob->r > kSoMaxR)
+    return fail(ctx, ACSE_ERR_UNSUPPORTED, "the NY adjoint runs up to r = " + std::to_string(kSoMaxR));
   for (const void *q : {static_cast<const void *>(Rbar_aa), static_cast<const void *>(Rbar_ab),
                         static_cast<const void *>(h_bar), static_cast<const void *>(V_bar),
                         static_cast<const void *>(d1_bar), static_cast<const void *>(d2aa_bar),
@@ -1927,6 +2145,10 @@ extern "C" acse_status acse_residual_vjp(acse_ctx ctx, const acse_problem *prob,
                          term(Wbaa, 0, 3, 1, 2, g, 2.0 / 3.0), term(Wbaa, 1, 2, 0, 3, g, 2.0 / 3.0),
                          term(Wbab, 0, 2, 1, 3, g, -2.0 / 3.0), term(Wbab, 1, 3, 0, 2, g, -2.0 / 3.0)},
                         gb, 1));
+  // the NY share's adjoint joins the accumulators before their projections
+  if (ctx->ny_on && (st = ny_vjp_share(ctx, prob, w.Aaa, w.Aab, Rbar_aa, Rbar_ab, Abaa, Abab, Gbaa, Gbab, gb)) !=
+                        ACSE_OK)
+    return st;
   // Gamma2-bar = G-bar (GEMM) + W-bar;  d2-bar = 2 Gamma2-bar (projected)
   HIP_TRY(ctx, permute(GEMM_F64, natref(Gbaa), false, Wbaa, ID, 1.0, nullptr, ID, 0.0, 1));
   HIP_TRY(ctx, permute(GEMM_F64, natref(Gbab), false, Wbab, ID, 1.0, nullptr, ID, 0.0, 1));
@@ -2072,8 +2294,9 @@ extern "C" acse_status acse_solve(acse_ctx ctx, acse_problem *prob, const acse_o
   if ((st = check_solve_options(ctx, so, res, hist, cap)) != ACSE_OK) return st;
   HIP_TRY(ctx, hipSetDevice(ctx->device));
   const bool quad = so->control == ACSE_EULER_QUADRATIC;
-  if (quad && ctx->ny_on)
-    return fail(ctx, ACSE_ERR_UNSUPPORTED, "the quadratic control needs the adjoint, built for the Valdemoro reconstruction only");
+  if (quad && ctx->ny_on && prob->r > kSoMaxR)
+    return fail(ctx, ACSE_ERR_UNSUPPORTED, "the quadratic control with NY needs the NY adjoint, which runs up to r = " +
+                                               std::to_string(kSoMaxR));
   if (ctx->crt_moduli && (st = ensure_crt(ctx)) != ACSE_OK) return st;
   SolveWs sw{};
   if ((st = ensure_solve_ws(ctx, quad, sw)) != ACSE_OK) return st;
@@ -2637,12 +2860,10 @@ extern "C" acse_status acse_autotune_batched(acse_ctx ctx, int32_t count, const 
 // taken once with weight 2.  17 r^2 x r^2 x r^2 FP64 products per map (Y 3,
 // the W H products 4, E 10), grouped in three launches.
 // ===========================================================================
-#include "spin.h"
 
 namespace {
 
 constexpr int kSpinNat = 50;   // natural r^4 arrays
-constexpr int kSpinNyMaxR = 64;  // the NY share's operand relayout stages n = 2r rows of n + 1 doubles in LDS
 constexpr int kSpinOps = 25;   // GEMM operand buffers
 enum { B0000 = 0, B0101 = 5, B0110 = 6, B1001 = 9, B1010 = 10, B1111 = 15 };
 constexpr int kSix[6] = {B0000, B1111, B0101, B1010, B0110, B1001};
@@ -2667,15 +2888,6 @@ struct SpinWs {
   // (allocated by the first acse_solve_spin call)
   void *kbase = nullptr;
   double *Nk[3] = {}, *gk[2] = {};
-  // the NY share over spin-orbital tensors (n = 2r spin orbitals): X, the
-  // 2-cumulant and its sigma-weighted copy, two intermediates, B, the two
-  // GEMM operands, Y and sigma (allocated by the first NY call for its r,
-  // grown when a larger r comes)
-  void *nybase = nullptr;
-  int ny_n = 0;
-  double *soX = nullptr, *soC2 = nullptr, *soCS = nullptr, *soW = nullptr, *soT = nullptr, *soB = nullptr;
-  double *soOpA = nullptr, *soOpB = nullptr, *soY = nullptr, *soSig = nullptr;
-  std::vector<double> so_sig;  // what soSig holds
 };
 
 acse_status ensure_spin_ws(acse_ctx c, SpinWs *&out) {
@@ -2756,9 +2968,9 @@ acse_status validate_spin(acse_ctx c, const acse_problem_spin *p, const acse_opt
     if (o->reconstruction != ACSE_RECON_V && o->reconstruction != ACSE_RECON_NY)
       return fail(c, ACSE_ERR_ARG, "unknown reconstruction");
     if (o->reconstruction == ACSE_RECON_NY) {
-      if (p->r > kSpinNyMaxR)
+      if (p->r > kSoMaxR)
         return fail(c, ACSE_ERR_UNSUPPORTED, "the NY share of the spin-block path runs up to r = " +
-                                                 std::to_string(kSpinNyMaxR));
+                                                 std::to_string(kSoMaxR));
       if (o->ny_sigma)
         for (int q = 0; q < 2 * p->r; ++q)
           if (o->ny_sigma[q] != 1 && o->ny_sigma[q] != -1)
@@ -2980,89 +3192,6 @@ acse_status spin_xa_from_blocks(acse_ctx c, SpinWs &w, int r, const double *Xaa,
   return ACSE_OK;
 }
 
-// Workspace of the spin-block NY share for n spin orbitals (kept; grown when
-// a larger n comes, after the stream has drained).
-acse_status ensure_spin_ny(acse_ctx c, SpinWs &w, int n) {
-  if (w.nybase && w.ny_n >= n) return ACSE_OK;
-  if (w.nybase) {
-    HIP_TRY(c, hipStreamSynchronize(c->stream));
-    (void)hipFree(w.nybase);
-    w.nybase = nullptr;
-    w.ny_n = 0;
-  }
-  const int64_t n2 = (int64_t)n * n;
-  const int64_t nat = round_up(n2 * n2 * 8, 256), opb = round_up(op_rows(n) * op_ld(n) * 8, 256);
-  const int64_t bytes = 6 * nat + 2 * opb + round_up(n2 * 8, 256) + round_up((int64_t)n * 8, 256);
-  if (hipMalloc(&w.nybase, bytes) != hipSuccess) {
-    (void)hipGetLastError();
-    w.nybase = nullptr;
-    return fail(c, ACSE_ERR_NOMEM, "cannot allocate the NY workspace of the spin-block path (" +
-                                       std::to_string(bytes) + " bytes)");
-  }
-  char *q = static_cast<char *>(w.nybase);
-  auto take = [&](int64_t b) { double *x = reinterpret_cast<double *>(q); q += b; return x; };
-  w.soX = take(nat); w.soC2 = take(nat); w.soCS = take(nat); w.soW = take(nat); w.soT = take(nat);
-  w.soB = take(nat);
-  w.soOpA = take(opb); w.soOpB = take(opb);
-  w.soY = take(round_up(n2 * 8, 256));
-  w.soSig = take(round_up((int64_t)n * 8, 256));
-  w.ny_n = n;
-  w.so_sig.clear();
-  return ACSE_OK;
-}
-
-// out[lo] = alpha sum A[la] B[lb] over natural n^4 arrays whose axes carry
-// the letters la, lb, lo (four distinct letters each): the two letters A and B
-// share and lo lacks are summed.  Both operands are relaid out as
-// [(two free letters)][(the two summed letters)], then one FP64 GEMM writes
-// through 4-index store strides.
-acse_status so_contract(acse_ctx c, SpinWs &w, int n, double *out, const char *lo, const double *A, const char *la,
-                        const double *B, const char *lb, double alpha) {
-  auto pos = [](const char *t, char ch) {
-    for (int k = 0; k < 4; ++k)
-      if (t[k] == ch) return k;
-    return -1;
-  };
-  const int64_t n2 = (int64_t)n * n;
-  const int64_t pw[4] = {n2 * n, n2, n, 1};
-  char fa[2], fb[2], kc[2];
-  int nfa = 0, nfb = 0, nk = 0;
-  for (int k = 0; k < 4; ++k) {
-    const char ch = lo[k];
-    const bool ia = pos(la, ch) >= 0, ib = pos(lb, ch) >= 0;
-    if (ia == ib || (ia ? nfa : nfb) == 2) return fail(c, ACSE_ERR_HIP, "internal: bad spin-orbital contraction");
-    (ia ? fa[nfa++] : fb[nfb++]) = ch;
-  }
-  for (int k = 0; k < 4; ++k) {
-    const char ch = la[k];
-    if (pos(lo, ch) >= 0) continue;
-    if (pos(lb, ch) < 0 || nk == 2) return fail(c, ACSE_ERR_HIP, "internal: bad spin-orbital contraction");
-    kc[nk++] = ch;
-  }
-  if (nfa != 2 || nfb != 2 || nk != 2) return fail(c, ACSE_ERR_HIP, "internal: bad spin-orbital contraction");
-  hipStream_t s = c->stream;
-  const int64_t rows = op_rows(n), ld = op_ld(n);
-  auto relayout = [&](const double *src, const char *ls, const char *f, double *dst) {
-    PermArgs a{};
-    a.r = n; a.rows = rows; a.ld = ld; a.src1 = src; a.c1 = 1.0;
-    const char order[4] = {f[0], f[1], kc[0], kc[1]};
-    for (int k = 0; k < 4; ++k) a.s1[k] = pw[pos(ls, order[k])];
-    return launch_permute4(GEMM_F64, a, OperandRef{dst, nullptr}, s);
-  };
-  HIP_TRY(c, relayout(A, la, fa, w.soOpA));
-  HIP_TRY(c, relayout(B, lb, fb, w.soOpB));
-  GemmBatch b{};
-  b.count = 1;
-  GemmProb &P = b.p[0];
-  P.A = w.soOpA; P.B = w.soOpB; P.C = out; P.alpha = alpha;
-  P.M = (int)n2; P.N = (int)n2; P.ld = (int)ld; P.Kp = gemm_kp(GEMM_F64, (int)n2, (int)ld); P.rdiv = n;
-  P.sm1 = pw[pos(lo, fa[0])]; P.sm0 = pw[pos(lo, fa[1])]; P.sn1 = pw[pos(lo, fb[0])]; P.sn0 = pw[pos(lo, fb[1])];
-  P.ksplit = 1; P.kchunk = P.Kp; P.accumulate = 0;
-  StageTimer t7(c, 7);  // the products alone
-  HIP_TRY(c, gemm_launch(GEMM_F64, gemm_default_cfg(GEMM_F64, (int)n2, (int)n2), b, s));
-  return ACSE_OK;
-}
-
 // The NY share of the spin-block map: S_b -= C_b for the three output blocks,
 // C = B - B(k<->l), B the contraction of X with the NY 3-cumulant of Eq. (8)
 // (App. D), in FP64 over spin-orbital tensors (n = 2r).  The 36 signed
@@ -3075,67 +3204,54 @@ acse_status so_contract(acse_ctx c, SpinWs &w, int n, double *out, const char *l
 // with c the 2-cumulant and cs = c with its first lower index a weighted by
 // sigma_a; each t is two pairwise contractions (n^6 each).  X is the map's
 // operator, antisymmetric in both pairs (the X_A blocks).
-acse_status ny_spin_share(acse_ctx c, SpinWs &w, const acse_problem_spin *p, const double *ga, const double *gb) {
+acse_status ny_spin_share(acse_ctx c, SpinWs &sw, const acse_problem_spin *p, const double *ga, const double *gb) {
   const int r = p->r, n = 2 * r;
   const int64_t n2 = (int64_t)n * n, n3 = n2 * n;
   hipStream_t s = c->stream;
   StageTimer t6(c, 6);
-  acse_status st = ensure_spin_ny(c, w, n);
+  SoWs *wp = nullptr;
+  acse_status st = ensure_so_ws(c, n, 6, wp);
   if (st != ACSE_OK) return st;
-  if (w.so_sig != c->ny_sigma) {
-    // the host copy stays in the workspace until the next change, after a synchronisation
-    HIP_TRY(c, hipStreamSynchronize(s));
-    w.so_sig = c->ny_sigma;
-    HIP_TRY(c, hipMemcpyAsync(w.soSig, w.so_sig.data(), (size_t)n * sizeof(double), hipMemcpyHostToDevice, s));
-  }
-  HIP_TRY(c, launch_fill(n2 * n2, 0.0, w.soX, s));
-  for (int b : kSix) HIP_TRY(c, launch_so_embed(r, b, w.XA[b], 1.0, w.soX, s));
-  HIP_TRY(c, launch_so_cumulant(r, ga, gb, p->d2aa, p->d2bb, p->d2ab, w.soSig, w.soC2, w.soCS, s));
-  auto t4 = [](const double *in, double cf, int64_t s0, int64_t s1, int64_t s2, int64_t s3) {
-    Term4 t{};
-    t.in = in; t.c = cf; t.s[0] = s0; t.s[1] = s1; t.s[2] = s2; t.s[3] = s3;
-    return t;
-  };
+  SoWs &w = *wp;
+  double *X = w.a[0], *C2 = w.a[1], *CS = w.a[2], *W = w.a[3], *T = w.a[4], *B = w.a[5];
+  if ((st = so_upload_sigma(c, w, c->ny_sigma)) != ACSE_OK) return st;
+  HIP_TRY(c, launch_fill(n2 * n2, 0.0, X, s));
+  for (int b : kSix) HIP_TRY(c, launch_so_embed(r, b, sw.XA[b], 1.0, X, s));
+  HIP_TRY(c, launch_so_cumulant(r, ga, gb, p->d2aa, p->d2bb, p->d2ab, w.sig, C2, CS, s));
   // x = i, y = l; then the p, l term through Y
-  if ((st = so_contract(c, w, n, w.soW, "kpia", w.soX, "kprq", w.soC2, "iarq", 1.0)) != ACSE_OK) return st;
-  HIP_TRY(c, launch_so_trace_y(n, w.soW, w.soY, s));
-  if ((st = so_contract(c, w, n, w.soT, "ijkl", w.soW, "kpia", w.soCS, "jpal", 1.0)) != ACSE_OK) return st;
+  if ((st = so_contract(c, w, n, W, "kpia", X, "kprq", C2, "iarq", 1.0)) != ACSE_OK) return st;
+  HIP_TRY(c, launch_so_trace_y(n, W, w.Y, s));
+  if ((st = so_contract(c, w, n, T, "ijkl", W, "kpia", CS, "jpal", 1.0)) != ACSE_OK) return st;
   {
-    Terms4 T{};
-    T.n = 2;
-    T.t[0] = t4(w.soT, 4.0, n3, n2, n, 1);
-    T.t[1] = t4(w.soT, -4.0, n2, n3, n, 1);
-    HIP_TRY(c, launch_combine4(n, T, w.soB, 0, nullptr, s));
+    Terms4 Q{};
+    Q.n = 2;
+    Q.t[0] = so_term(T, 4.0, n3, n2, n, 1);
+    Q.t[1] = so_term(T, -4.0, n2, n3, n, 1);
+    HIP_TRY(c, launch_combine4(n, Q, B, 0, nullptr, s));
   }
-  HIP_TRY(c, launch_so_tpl(n, 4.0, w.soY, w.soCS, w.soB, s));
+  HIP_TRY(c, launch_so_tpl(n, 4.0, w.Y, CS, B, s));
   // x = i, y = r (the y = q products equal these)
-  if ((st = so_contract(c, w, n, w.soW, "kqja", w.soX, "kprq", w.soCS, "jpar", 1.0)) != ACSE_OK) return st;
-  if ((st = so_contract(c, w, n, w.soT, "ijkl", w.soW, "kqja", w.soC2, "ialq", 1.0)) != ACSE_OK) return st;
+  if ((st = so_contract(c, w, n, W, "kqja", X, "kprq", CS, "jpar", 1.0)) != ACSE_OK) return st;
+  if ((st = so_contract(c, w, n, T, "ijkl", W, "kqja", C2, "ialq", 1.0)) != ACSE_OK) return st;
   {
-    Terms4 T{};
-    T.n = 2;
-    T.t[0] = t4(w.soT, -8.0, n3, n2, n, 1);
-    T.t[1] = t4(w.soT, 8.0, n2, n3, n, 1);
-    HIP_TRY(c, launch_combine4(n, T, w.soB, 1, nullptr, s));
+    Terms4 Q{};
+    Q.n = 2;
+    Q.t[0] = so_term(T, -8.0, n3, n2, n, 1);
+    Q.t[1] = so_term(T, 8.0, n2, n3, n, 1);
+    HIP_TRY(c, launch_combine4(n, Q, B, 1, nullptr, s));
   }
-  // x = p, y = r
-  if ((st = so_contract(c, w, n, w.soW, "kral", w.soX, "kprq", w.soC2, "palq", 1.0)) != ACSE_OK) return st;
-  if ((st = so_contract(c, w, n, w.soT, "ijkl", w.soW, "kral", w.soCS, "ijar", 1.0)) != ACSE_OK) return st;
-  {
-    Terms4 T{};
-    T.n = 1;
-    T.t[0] = t4(w.soT, -8.0, n3, n2, n, 1);
-    HIP_TRY(c, launch_combine4(n, T, w.soB, 1, nullptr, s));
-  }
+  // x = p, y = r: accumulated straight into B
+  if ((st = so_contract(c, w, n, W, "kral", X, "kprq", C2, "palq", 1.0)) != ACSE_OK) return st;
+  if ((st = so_contract(c, w, n, B, "ijkl", W, "kral", CS, "ijar", -8.0, 1)) != ACSE_OK) return st;
   // S_b -= B_b - B_b(k<->l) on the spin block b of B
   for (int b : {B0000, B1111, B0101}) {
     const int64_t o0 = ((b >> 3) & 1) * (int64_t)r * n3, o1 = ((b >> 2) & 1) * (int64_t)r * n2;
     const int64_t o2 = ((b >> 1) & 1) * (int64_t)r, o3 = (b & 1) * (int64_t)r;
-    Terms4 T{};
-    T.n = 2;
-    T.t[0] = t4(w.soB + o0 + o1 + o2 * n + o3, -1.0, n3, n2, n, 1);
-    T.t[1] = t4(w.soB + o0 + o1 + o3 * n + o2, 1.0, n3, n2, 1, n);
-    HIP_TRY(c, launch_combine4(r, T, w.S[b], 1, nullptr, s));
+    Terms4 Q{};
+    Q.n = 2;
+    Q.t[0] = so_term(B + o0 + o1 + o2 * n + o3, -1.0, n3, n2, n, 1);
+    Q.t[1] = so_term(B + o0 + o1 + o3 * n + o2, 1.0, n3, n2, 1, n);
+    HIP_TRY(c, launch_combine4(r, Q, sw.S[b], 1, nullptr, s));
   }
   return ACSE_OK;
 }
@@ -3637,7 +3753,6 @@ void release_spin_ws(acse_ctx c) {
   SpinWs *w = static_cast<SpinWs *>(c->spws);
   if (w && w->cbase) (void)hipFree(w->cbase);
   if (w && w->kbase) (void)hipFree(w->kbase);
-  if (w && w->nybase) (void)hipFree(w->nybase);
   delete w;
   c->spws = nullptr;
 }

@@ -69,4 +69,37 @@ hipError_t launch_so_trace_y(int n, const double *W, double *Y, hipStream_t s);
 // B[i,j,k,l] += c sum_a Y[k,a] cs[i,j,a,l].
 hipError_t launch_so_tpl(int n, double c, const double *Y, const double *cs, double *B, hipStream_t s);
 
+// ---- the NY share's adjoint on singlet states (spin-orbital, n = 2r) ---------
+// X (all n^4 elements) from the fold's blocks: same-spin blocks Aaa, the
+// (ab|ab) and (ba|ba) blocks Aab, the (ab|ba) and (ba|ab) blocks -Aab with the
+// lower pair exchanged; zero elsewhere.
+hipError_t launch_so_embed_singlet_x(int r, const double *Aaa, const double *Aab, double *X, hipStream_t s);
+// Abaa += Xbar(aa|aa) + Xbar(bb|bb); Abab += Xbar(ab|ab) + Xbar(ba|ba)
+// - Xbar(ab|ba) - Xbar(ba|ab) (the last two with the lower pair exchanged):
+// the adjoint of the embedding above.
+hipError_t launch_so_xbar_singlet(int r, const double *Xbar, double *Abaa, double *Abab, hipStream_t s);
+// Adjoint of the singlet lift of the 2-RDM blocks, scaled by c and added:
+// Gaa += c (D(aa|aa) + D(bb|bb)), Gab[p,q,s,t] += c (D(ab|ab)[p,q,s,t] +
+// D(ba|ba)[q,p,t,s] - D(ab|ba)[p,q,t,s] - D(ba|ab)[q,p,s,t]).
+hipError_t launch_so_dbar_singlet(int r, double c, const double *D, double *Gaa, double *Gab, hipStream_t s);
+// Cotangent of B from that of F: Bbar = -Rbar + Rbar' + Rbar(k<->l) - Rbar'(k<->l)
+// for sign = +1 (Hermitian X: F carries -C + C'), with the two exchanged terms
+// negated for sign = -1; ' exchanges (ij) and (kl).  Rbar is nonzero on the
+// (aa|aa) block (Rbar_aa) and the (ab|ab) block (Rbar_ab) only.
+hipError_t launch_so_bbar(int r, const double *Rbar_aa, const double *Rbar_ab, double sign, double *Bbar,
+                          hipStream_t s);
+// Ybar[k,a] = c sum_{i,j,l} Bbar[i,j,k,l] cs[i,j,a,l] (fixed summation order).
+hipError_t launch_so_ybar(int n, double c, const double *Bbar, const double *cs, double *Ybar, hipStream_t s);
+// CSbar[i,j,a,l] += c sum_k Bbar[i,j,k,l] Y[k,a].
+hipError_t launch_so_csbar_pl(int n, double c, const double *Bbar, const double *Y, double *CSbar, hipStream_t s);
+// Wbar[k,p,p,a] += Ybar[k,a] for every p (adjoint of the trace Y = sum_p W[k,p,p,a]).
+hipError_t launch_so_diag_add(int n, const double *Ybar, double *Wbar, hipStream_t s);
+// C2bar += sig[a] CSbar, a the third index (adjoint of cs = sigma_a c2).
+hipError_t launch_so_sigma_fold(int n, const double *sig, const double *CSbar, double *C2bar, hipStream_t s);
+// gbar[x,y] += Dbar1[x,y] + Dbar1[x+r,y+r], the adjoint of the cumulant's
+// wedge term through the 1-RDM diag(g, g):
+// Dbar1[X,Y] = -1/2 [sum c[X,J,Y,Q] D1[J,Q] + sum c[I,X,R,Y] D1[I,R]
+//                    - sum c[I,X,Y,Q] D1[I,Q] - sum c[X,J,R,Y] D1[J,R]].
+hipError_t launch_so_d1bar_singlet(int r, const double *g, const double *C2bar, double *gbar, hipStream_t s);
+
 }  // namespace acse

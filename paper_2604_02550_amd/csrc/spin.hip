@@ -216,6 +216,143 @@ k_so_tpl(int n, double c, const double *__restrict__ Y, const double *__restrict
   B[e] += c * acc;
 }
 
+// ---- adjoint of the NY share on singlet states ------------------------------
+__global__ void __launch_bounds__(256)
+k_so_embed_singlet_x(int r, const double *__restrict__ Aaa, const double *__restrict__ Aab, double *__restrict__ X) {
+  const int64_t n = 2 * (int64_t)r, n2 = n * n;
+  const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (e >= n2 * n2) return;
+  const int L = (int)(e % n), K = (int)((e / n) % n), J = (int)((e / n2) % n), I = (int)(e / (n2 * n));
+  const int si = I >= r, sj = J >= r, sk = K >= r, sl = L >= r;
+  const int i = I - si * r, j = J - sj * r, k = K - sk * r, l = L - sl * r;
+  const int64_t r2 = (int64_t)r * r;
+  const int64_t nat = ((int64_t)i * r + j) * r2 + (int64_t)k * r + l;
+  const int64_t swp = ((int64_t)i * r + j) * r2 + (int64_t)l * r + k;
+  double v = 0.0;
+  switch ((si << 3) | (sj << 2) | (sk << 1) | sl) {
+    case 0x0: case 0xF: v = Aaa[nat]; break;
+    case 0x5: case 0xA: v = Aab[nat]; break;
+    case 0x6: case 0x9: v = -Aab[swp]; break;
+    default: break;
+  }
+  X[e] = v;
+}
+
+__global__ void __launch_bounds__(256)
+k_so_xbar_singlet(int r, const double *__restrict__ Xb, double *__restrict__ Abaa, double *__restrict__ Abab) {
+  const int64_t r2 = (int64_t)r * r;
+  const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (e >= r2 * r2) return;
+  const int l = (int)(e % r), k = (int)((e / r) % r), j = (int)((e / r2) % r), i = (int)(e / (r2 * r));
+  const int64_t n = 2 * (int64_t)r;
+  auto at = [&](int a, int b, int c, int d) { return Xb[((a * n + b) * n + c) * n + d]; };
+  Abaa[e] += at(i, j, k, l) + at(i + r, j + r, k + r, l + r);
+  Abab[e] += at(i, j + r, k, l + r) + at(i + r, j, k + r, l) - at(i, j + r, l + r, k) - at(i + r, j, l, k + r);
+}
+
+__global__ void __launch_bounds__(256)
+k_so_dbar_singlet(int r, double c, const double *__restrict__ D, double *__restrict__ Gaa, double *__restrict__ Gab) {
+  const int64_t r2 = (int64_t)r * r;
+  const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (e >= r2 * r2) return;
+  // output element [p,q,u,t]
+  const int t = (int)(e % r), u = (int)((e / r) % r), q = (int)((e / r2) % r), p = (int)(e / (r2 * r));
+  const int64_t n = 2 * (int64_t)r;
+  auto at = [&](int w, int x, int y, int z) { return D[((w * n + x) * n + y) * n + z]; };
+  Gaa[e] += c * (at(p, q, u, t) + at(p + r, q + r, u + r, t + r));
+  Gab[e] += c * (at(p, q + r, u, t + r) + at(q + r, p, t + r, u) - at(p, q + r, t + r, u) -
+                 at(q + r, p, u, t + r));
+}
+
+__global__ void __launch_bounds__(256)
+k_so_bbar(int r, const double *__restrict__ Raa, const double *__restrict__ Rab, double sign, double *__restrict__ Bb) {
+  const int64_t n = 2 * (int64_t)r, n2 = n * n;
+  const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (e >= n2 * n2) return;
+  const int L = (int)(e % n), K = (int)((e / n) % n), J = (int)((e / n2) % n), I = (int)(e / (n2 * n));
+  const int64_t r2 = (int64_t)r * r;
+  // the cotangent of the spin-orbital residual: Rbar_aa on (aa|aa), Rbar_ab on (ab|ab)
+  auto rb = [&](int a, int b, int c, int d) -> double {
+    const int sa = a >= r, sb = b >= r, sc = c >= r, sd = d >= r;
+    const int64_t x = ((int64_t)(a - sa * r) * r + (b - sb * r)) * r2 + (int64_t)(c - sc * r) * r + (d - sd * r);
+    const int code = (sa << 3) | (sb << 2) | (sc << 1) | sd;
+    return code == 0 ? Raa[x] : code == 5 ? Rab[x] : 0.0;
+  };
+  Bb[e] = -rb(I, J, K, L) + rb(I, J, L, K) + sign * (rb(K, L, I, J) - rb(L, K, I, J));
+}
+
+// One workgroup of 256 per (k, a); the threads stride over (i, j, l) with l
+// fastest, then a fixed-order reduction.
+__global__ void __launch_bounds__(256)
+k_so_ybar(int n, double c, const double *__restrict__ Bb, const double *__restrict__ cs, double *__restrict__ Yb) {
+  __shared__ double part[4];
+  const int k = blockIdx.x / n, a = blockIdx.x % n;
+  const int64_t n2 = (int64_t)n * n, tot = n2 * n;
+  double acc = 0.0;
+  for (int64_t e = threadIdx.x; e < tot; e += 256) {
+    const int64_t ij = e / n;
+    const int l = (int)(e - ij * n);
+    acc += Bb[ij * n2 + (int64_t)k * n + l] * cs[ij * n2 + (int64_t)a * n + l];
+  }
+  for (int off = 32; off > 0; off >>= 1) acc += __shfl_down(acc, off, 64);
+  if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = acc;
+  __syncthreads();
+  if (threadIdx.x == 0) Yb[blockIdx.x] = c * (((part[0] + part[1]) + part[2]) + part[3]);
+}
+
+__global__ void __launch_bounds__(256)
+k_so_csbar_pl(int n, double c, const double *__restrict__ Bb, const double *__restrict__ Y, double *__restrict__ CSb) {
+  const int64_t n2 = (int64_t)n * n;
+  const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (e >= n2 * n2) return;
+  const int l = (int)(e % n), a = (int)((e / n) % n);
+  const int64_t ij = e / n2;
+  const double *b = Bb + ij * n2 + l;
+  double acc = 0.0;
+  for (int k = 0; k < n; ++k) acc += b[(int64_t)k * n] * Y[(int64_t)k * n + a];
+  CSb[e] += c * acc;
+}
+
+__global__ void __launch_bounds__(256) k_so_diag_add(int n, const double *__restrict__ Yb, double *__restrict__ Wb) {
+  const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (e >= (int64_t)n * n * n) return;
+  const int a = (int)(e % n), p = (int)((e / n) % n), k = (int)(e / ((int64_t)n * n));
+  const int64_t n2 = (int64_t)n * n;
+  Wb[((int64_t)k * n + p) * n2 + (int64_t)p * n + a] += Yb[(int64_t)k * n + a];
+}
+
+__global__ void __launch_bounds__(256)
+k_so_sigma_fold(int n, const double *__restrict__ sig, const double *__restrict__ CSb, double *__restrict__ C2b) {
+  const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (e >= (int64_t)n * n * n * n) return;
+  C2b[e] += sig[(e / n) % n] * CSb[e];
+}
+
+// One thread per spatial (x, y): both spin blocks of the output, each sum over
+// the nonzero (same-spin) entries of D1 = diag(g, g).
+__global__ void __launch_bounds__(256)
+k_so_d1bar_singlet(int r, const double *__restrict__ g, const double *__restrict__ cb, double *__restrict__ gb) {
+  const int e = blockIdx.x * 256 + threadIdx.x;
+  if (e >= r * r) return;
+  const int x = e / r, y = e % r;
+  const int64_t n = 2 * (int64_t)r;
+  auto at = [&](int64_t a, int64_t b, int64_t c, int64_t d) { return cb[((a * n + b) * n + c) * n + d]; };
+  double tot = 0.0;
+  for (int sx = 0; sx < 2; ++sx) {
+    const int64_t X = x + sx * r, Y = y + sx * r;
+    double acc = 0.0;
+    for (int sj = 0; sj < 2; ++sj)
+      for (int j = 0; j < r; ++j)
+        for (int q = 0; q < r; ++q) {
+          const double d = g[j * r + q];
+          const int64_t J = j + sj * r, Q = q + sj * r;
+          acc += d * (at(X, J, Y, Q) + at(J, X, Q, Y) - at(J, X, Y, Q) - at(X, J, Q, Y));
+        }
+    tot += -0.5 * acc;
+  }
+  gb[e] += tot;
+}
+
 inline dim3 grid1(int64_t n) { return dim3((unsigned)((n + 255) / 256)); }
 
 }  // namespace
@@ -285,6 +422,54 @@ hipError_t launch_so_trace_y(int n, const double *W, double *Y, hipStream_t s) {
 
 hipError_t launch_so_tpl(int n, double c, const double *Y, const double *cs, double *B, hipStream_t s) {
   hipLaunchKernelGGL(k_so_tpl, grid1((int64_t)n * n * n * n), dim3(256), 0, s, n, c, Y, cs, B);
+  return hipGetLastError();
+}
+
+hipError_t launch_so_embed_singlet_x(int r, const double *Aaa, const double *Aab, double *X, hipStream_t s) {
+  const int64_t n = 2 * (int64_t)r;
+  hipLaunchKernelGGL(k_so_embed_singlet_x, grid1(n * n * n * n), dim3(256), 0, s, r, Aaa, Aab, X);
+  return hipGetLastError();
+}
+
+hipError_t launch_so_xbar_singlet(int r, const double *Xbar, double *Abaa, double *Abab, hipStream_t s) {
+  hipLaunchKernelGGL(k_so_xbar_singlet, grid1((int64_t)r * r * r * r), dim3(256), 0, s, r, Xbar, Abaa, Abab);
+  return hipGetLastError();
+}
+
+hipError_t launch_so_dbar_singlet(int r, double c, const double *D, double *Gaa, double *Gab, hipStream_t s) {
+  hipLaunchKernelGGL(k_so_dbar_singlet, grid1((int64_t)r * r * r * r), dim3(256), 0, s, r, c, D, Gaa, Gab);
+  return hipGetLastError();
+}
+
+hipError_t launch_so_bbar(int r, const double *Rbar_aa, const double *Rbar_ab, double sign, double *Bbar,
+                          hipStream_t s) {
+  const int64_t n = 2 * (int64_t)r;
+  hipLaunchKernelGGL(k_so_bbar, grid1(n * n * n * n), dim3(256), 0, s, r, Rbar_aa, Rbar_ab, sign, Bbar);
+  return hipGetLastError();
+}
+
+hipError_t launch_so_ybar(int n, double c, const double *Bbar, const double *cs, double *Ybar, hipStream_t s) {
+  hipLaunchKernelGGL(k_so_ybar, dim3((unsigned)(n * n)), dim3(256), 0, s, n, c, Bbar, cs, Ybar);
+  return hipGetLastError();
+}
+
+hipError_t launch_so_csbar_pl(int n, double c, const double *Bbar, const double *Y, double *CSbar, hipStream_t s) {
+  hipLaunchKernelGGL(k_so_csbar_pl, grid1((int64_t)n * n * n * n), dim3(256), 0, s, n, c, Bbar, Y, CSbar);
+  return hipGetLastError();
+}
+
+hipError_t launch_so_diag_add(int n, const double *Ybar, double *Wbar, hipStream_t s) {
+  hipLaunchKernelGGL(k_so_diag_add, grid1((int64_t)n * n * n), dim3(256), 0, s, n, Ybar, Wbar);
+  return hipGetLastError();
+}
+
+hipError_t launch_so_sigma_fold(int n, const double *sig, const double *CSbar, double *C2bar, hipStream_t s) {
+  hipLaunchKernelGGL(k_so_sigma_fold, grid1((int64_t)n * n * n * n), dim3(256), 0, s, n, sig, CSbar, C2bar);
+  return hipGetLastError();
+}
+
+hipError_t launch_so_d1bar_singlet(int r, const double *g, const double *C2bar, double *gbar, hipStream_t s) {
+  hipLaunchKernelGGL(k_so_d1bar_singlet, grid1((int64_t)r * r), dim3(256), 0, s, r, g, C2bar, gbar);
   return hipGetLastError();
 }
 

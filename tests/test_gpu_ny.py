@@ -24,8 +24,9 @@ test_oracle_ny.py).
   the FP64 bar (residual, share, step; r = 50 stored values).
 * The batched residual with the NY 3-RDM (instances of r = 6, 9, 13 in one
   call) against the oracle per instance.
-* Rejected combinations: the adjoint, the quadratic control, an explicit
-  sigma array in a batch, sigma entries other than +1 / -1.
+* Rejected combinations: an explicit sigma array in a batch, sigma entries
+  other than +1 / -1; above r = 64 the adjoint, the quadratic control and the
+  spin-block path (their spin-orbital tensors).
 * Edges: r = 2 and 3; the step with the active-active mask on the
   general-size kernels; the update map on an anti-Hermitian direction that is
   not a residual; the backtracking control (rejected trials) with the input
@@ -185,6 +186,15 @@ def test_ny_r96_determinant(acse):
         scale = max(np.abs(exp_aa).max(), np.abs(exp_ab).max())
         assert np.abs(Raa.cpu().numpy() - exp_aa).max() <= 1e-10 * scale
         assert np.abs(Rab.cpu().numpy() - exp_ab).max() <= 1e-10 * scale
+        # the NY adjoint, the quadratic control with NY and the spin-block NY
+        # share run their spin-orbital tensors up to r = 64
+        with pytest.raises(acse.AcseError, match="UNSUPPORTED"):
+            ctx.residual_vjp(*inputs, na, Raa, Rab, sigma=True)
+        with pytest.raises(acse.AcseError, match="UNSUPPORTED"):
+            ctx.solve(*inputs, na, control="quadratic", sigma=True, max_iter=1)
+        with pytest.raises(acse.AcseError, match="UNSUPPORTED"):
+            ctx.residual_spin(inputs[0], inputs[1], inputs[2], inputs[2], inputs[3], inputs[3], inputs[4], na,
+                              na, sigma=True)
     finally:
         ctx.close()
 
@@ -200,13 +210,6 @@ def test_ny_rejected_combinations(acse):
         bp, bkeep = ctx.problem(p["h"], p["V"], p["gamma"], p["d2aa"], p["d2ab"], 2)
         with pytest.raises(acse.AcseError, match="ny_sigma must be NULL"):
             ctx.residual_batched_raw([bp], ctx.options("fp64", sigma=[1, 1, -1, -1]), [z[0]], [z[1]])
-        with pytest.raises(acse.AcseError, match="quadratic"):
-            ctx.solve(p["h"], p["V"], p["gamma"], p["d2aa"], p["d2ab"], 2, control="quadratic", sigma=True)
-        prob, keep = ctx.problem(p["h"], p["V"], p["gamma"], p["d2aa"], p["d2ab"], 2)
-        zs = [torch.zeros((4, 4), dtype=torch.float64, device="cuda") for _ in range(2)]
-        opts = ctx.options("fp64", sigma=True)
-        with pytest.raises(acse.AcseError, match="adjoint"):
-            ctx.residual_vjp_raw(prob, opts, z[0], z[1], zs[0], z[2], zs[1], z[3], z[4])
         # the Valdemoro path is unaffected afterwards
         Raa, Rab, n2 = ctx.residual(p["h"], p["V"], p["gamma"], p["d2aa"], p["d2ab"], 2)
         o = ost.residual(p["h"], p["V"], 4, p["gamma"], p["d2aa"], p["d2ab"])

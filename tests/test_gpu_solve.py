@@ -117,6 +117,37 @@ def test_solve_matches_oracle(ctx, name, control, eps, active, iters):
     assert g["maps"] >= 1 + steps + len(o["trials"])
 
 
+NY_QUAD_CASES = [("r6", 1e-2, 3), ("r10", 1e-3, 4), ("r13", 1e-2, 3)]
+
+
+@pytest.mark.parametrize("name,eps,iters", NY_QUAD_CASES)
+def test_solve_quadratic_ny_matches_oracle(ctx, name, eps, iters):
+    """The quadratic control with the NY 3-RDM: its slope comes from the NY
+    adjoint.  Interpolated second step sizes, rejected first trials and (r13)
+    halvings after a rejected pair; bars as for the Valdemoro quadratic runs."""
+    p = PROBLEMS[name]()
+    r = p["r"]
+    sig = [1 if q < p["N"] // 2 else -1 for q in range(r)]
+    print(f"[solve ny] {name} quadratic eps={eps} max_iter={iters}", flush=True)
+    o = sv.euler(p["h"], p["V"], p["N"], p["gamma"], p["d2aa"], p["d2ab"], eps=eps, de_tol=1e-9,
+                 max_iter=iters, control=2, max_halvings=12, sigma=sig)
+    assert margins_ok(o, 1e-6), "oracle decision too close to call"
+    g = ctx.solve(p["h"], p["V"], p["gamma"], p["d2aa"], p["d2ab"], p["N"] // 2, eps=eps, de_tol=1e-9,
+                  max_iter=iters, control="quadratic", max_halvings=12, sigma=True)
+    assert g["stop"] == STOPS[o["stop"]]
+    assert g["iterations"] == o["iterations"]
+    assert len(g["trials"]) == len(o["trials"]) == g["trial_count"]
+    for (ge, gE, gf, gn, ga), (oe, oE, of, on, oa) in zip(g["trials"], o["trials"]):
+        assert gn == on and ga == oa
+        assert abs(ge - oe) <= 1e-7 * abs(oe)
+        assert abs(gE - oE) <= 1e-8 * max(1.0, abs(oE))
+        assert abs(gf - of) <= 1e-8 * of
+    for key in ("d2aa", "d2ab", "gamma"):
+        x = g["d1" if key == "gamma" else key].cpu().numpy()
+        y = o[key]
+        assert np.abs(x - y).max() <= 1e-8 * np.abs(y).max(), key
+
+
 def test_solve_history_capacity(ctx):
     p = PROBLEMS["r6"]()
     full = ctx.solve(p["h"], p["V"], p["gamma"], p["d2aa"], p["d2ab"], p["N"] // 2, eps=0.1, de_tol=0.0,

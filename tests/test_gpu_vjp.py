@@ -10,6 +10,9 @@
   (1e-10 against the oracle adjoint, the r = 30 finite differences at 1e-7).
 * The torch.autograd.Function wrappers give the same gradients, and two calls
   are bitwise identical.
+* With the NY 3-RDM (default and non-prefix occupations): FP64 and the int8
+  products against the oracle's NY adjoint at 1e-10, and the autograd
+  wrapper with sigma.
 """
 import numpy as np
 import pytest
@@ -69,9 +72,9 @@ PROBLEMS = {
 }
 
 
-def gpu_vjp(ctx, p, Rb, precision="fp64"):
+def gpu_vjp(ctx, p, Rb, precision="fp64", sigma=None):
     out = ctx.residual_vjp(p["h"], p["V"], p["gamma"], p["d2aa"], p["d2ab"], p["N"] // 2,
-                           Rb[0], Rb[1], precision=precision)
+                           Rb[0], Rb[1], precision=precision, sigma=sigma)
     return dict(zip(KEYS, [cpu(x) for x in out]))
 
 
@@ -244,3 +247,59 @@ def test_vjp_argument_errors(acse, ctx):
     assert st == 1   # ACSE_ERR_ARG
     with pytest.raises(acse.AcseError):
         ctx.energy_vjp_raw(prob, float("nan"), out[0], out[1], out[3], out[4])
+
+
+def ny_sigma(p, kind):
+    """Default occupations (orbitals below N/2) or a non-prefix pattern."""
+    r, na = p["r"], p["N"] // 2
+    if kind == "default":
+        return [1 if q < na else -1 for q in range(r)]
+    return [1 if (q * 7 + 3) % r < na else -1 for q in range(r)]
+
+
+@pytest.mark.parametrize("kind", ["default", "scattered"])
+@pytest.mark.parametrize("name", list(PROBLEMS))
+def test_residual_vjp_ny_fp64_vs_oracle(ctx, name, kind):
+    """The NY adjoint (the Valdemoro adjoint plus the NY share's, FP64 over
+    spin-orbital tensors) against autograd of the oracle's NY residual."""
+    p = PROBLEMS[name]()
+    sig = ny_sigma(p, kind)
+    print(f"[residual_vjp_ny] {name} r={p['r']} sigma={sig}", flush=True)
+    Rb = gen.cotangent(np.random.default_rng(31), p["r"])
+    ref = adj.residual_vjp(p["h"], p["V"], p["N"], p["gamma"], p["d2aa"], p["d2ab"], *Rb, sigma=sig)
+    got = gpu_vjp(ctx, p, Rb, sigma=sig if kind != "default" else True)
+    for k in KEYS:
+        assert rel(got[k], ref[k]) < TOL64, (k, rel(got[k], ref[k]))
+        assert maxrel(got[k], ref[k]) < TOL64, (k, maxrel(got[k], ref[k]))
+    # the NY share's adjoint is not zero here
+    val = adj.residual_vjp(p["h"], p["V"], p["N"], p["gamma"], p["d2aa"], p["d2ab"], *Rb)
+    assert max(rel(val[k], ref[k]) for k in KEYS) > 1e-6
+
+
+def test_residual_vjp_ny_int8crt_vs_oracle(ctx):
+    p = PROBLEMS["r10"]()
+    sig = ny_sigma(p, "scattered")
+    print("[residual_vjp_ny] r10 int8crt", flush=True)
+    Rb = gen.cotangent(np.random.default_rng(32), p["r"])
+    ref = adj.residual_vjp(p["h"], p["V"], p["N"], p["gamma"], p["d2aa"], p["d2ab"], *Rb, sigma=sig)
+    got = gpu_vjp(ctx, p, Rb, "int8crt", sigma=sig)
+    for k in KEYS:
+        assert rel(got[k], ref[k]) < TOL64, (k, rel(got[k], ref[k]))
+        assert maxrel(got[k], ref[k]) < TOL64, (k, maxrel(got[k], ref[k]))
+
+
+def test_autograd_function_ny(acse, ctx):
+    import torch
+    p = PROBLEMS["r6"]()
+    sig = ny_sigma(p, "scattered")
+    dev = ctx.device
+    x = [torch.tensor(p[k], device=dev, requires_grad=True) for k in KEYS]
+    Rb = [torch.tensor(a, device=dev) for a in gen.cotangent(np.random.default_rng(33), p["r"])]
+    Raa, Rab = acse.ACSEResidual.apply(ctx, *x, p["N"] // 2, "fp64", sig)
+    o = ost.residual(p["h"], p["V"], p["N"], p["gamma"], p["d2aa"], p["d2ab"], sigma=sig)
+    assert np.abs(cpu(Raa) - o[0]).max() <= TOL64 * np.abs(o[0]).max()
+    ((Rb[0] * Raa).sum() + (Rb[1] * Rab).sum()).backward()
+    ref = adj.residual_vjp(p["h"], p["V"], p["N"], p["gamma"], p["d2aa"], p["d2ab"], *[cpu(t) for t in Rb],
+                           sigma=sig)
+    for t, k in zip(x, KEYS):
+        assert rel(cpu(t.grad), ref[k]) < TOL64, k
