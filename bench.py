@@ -444,8 +444,9 @@ def bench_spin(acse, ctx, gen, torch, steps, warmup, eps, mode="fp64", name="r50
               "gemm_nt_kernel<TrF64> on the 17 spin-block products per map (HIP-event time of their launches)")
     extra = {}
     if ny:
-        n = 2 * r
-        ny_flops = 2 * 6 * 2 * n ** 6          # two maps, six n^2 x n^2 x n^2 GEMMs each
+        # two maps; six spin-orbital contractions each, of which ten r^2 x r^2 x r^2
+        # spin-block products per contraction conserve spin and run
+        ny_flops = 2 * 6 * 10 * 2 * r ** 6
         ny_ms, _ = prof["ny_share"]
         nyg_ms, _ = prof["ny_gemm"]
         extra = dict(ny_share_ms_per_step=ny_ms / steps, ny_gemm_ms_per_step=nyg_ms / steps,

@@ -1466,7 +1466,14 @@ struct SoWs {
   double *a[kSoMaxArrays] = {};
   double *opA = nullptr, *opB = nullptr, *Y = nullptr, *Yb = nullptr, *sig = nullptr;
   std::vector<double> sig_host;  // what sig holds
+  int op_r = 0;                  // r whose operand layout the padding of opA / opB was cleared for
 };
+
+// Spin-blocked operand of r spatial orbitals: 4 row blocks of rpad rows, 4
+// column chunks of kc columns (one per spin pair of the row / summed letters).
+int64_t so_rpad(int r) { return round_up((int64_t)r * r, kRowPad); }
+int64_t so_kc(int r) { return round_up((int64_t)r * r, kKPad); }
+int64_t so_op_doubles(int r) { return 4 * so_rpad(r) * 4 * so_kc(r); }
 
 acse_status ensure_so_ws(acse_ctx c, int n, int narr, SoWs *&out) {
   SoWs *w = static_cast<SoWs *>(c->sows);
@@ -1485,7 +1492,7 @@ acse_status ensure_so_ws(acse_ctx c, int n, int narr, SoWs *&out) {
     w->n = w->narr = 0;
   }
   const int64_t n2 = (int64_t)nn * nn;
-  const int64_t nat = round_up(n2 * n2 * 8, 256), opb = round_up(op_rows(nn) * op_ld(nn) * 8, 256);
+  const int64_t nat = round_up(n2 * n2 * 8, 256), opb = round_up(so_op_doubles(nn / 2) * 8, 256);
   const int64_t sm = round_up(n2 * 8, 256);
   const int64_t bytes = na * nat + 2 * opb + 2 * sm + round_up((int64_t)nn * 8, 256);
   if (hipMalloc(&w->base, bytes) != hipSuccess) {
@@ -1505,6 +1512,7 @@ acse_status ensure_so_ws(acse_ctx c, int n, int narr, SoWs *&out) {
   w->n = nn;
   w->narr = na;
   w->sig_host.clear();
+  w->op_r = 0;
   return ACSE_OK;
 }
 
@@ -1527,21 +1535,37 @@ acse_status so_upload_sigma(acse_ctx c, SoWs &w, const std::vector<double> &sig)
   return ACSE_OK;
 }
 
-// out[lo] (+)= alpha sum A[la] B[lb] over natural n^4 arrays whose axes carry
-// the letters la, lb, lo (four distinct letters each): the two letters A and B
-// share and lo lacks are summed.  Both operands are relaid out as
-// [(two free letters)][(the two summed letters)], then one FP64 GEMM writes
-// through 4-index store strides (accumulating if acc).
+// Spin conservation of a spin-orbital tensor: an element is zero unless the
+// beta count of positions {0, pair} equals that of the other two positions
+// (pair = 1 for the tensors [upper pair][lower pair]; an intermediate such as
+// sum_pr X^{kp}_{rq} cs^{jp}_{ar} -> [k,q,j,a] conserves over {0, 3}).
+bool so_block_nonzero(int pair, const int sp[4]) {
+  int o[2], k = 0;
+  for (int t = 1; t < 4; ++t)
+    if (t != pair) o[k++] = t;
+  return sp[0] + sp[pair] == sp[o[0]] + sp[o[1]];
+}
+
+// out[lo] (+)= alpha sum A[la] B[lb] over natural n^4 arrays (n = 2r) whose
+// axes carry the letters la, lb, lo (four distinct letters each): the two
+// letters A and B share and lo lacks are summed.  pa, pb: the conservation
+// pairs of A and B (so_block_nonzero).  Both operands are packed spin-block
+// major ([spins of the two free letters][spins of the two summed letters],
+// r^2 x r^2 blocks); one r^2 x r^2 x r^2 FP64 product runs per output spin
+// block and summed spin pair whose A and B blocks both conserve spin, written
+// through 4-index store strides into its spin block of out.  Without acc the
+// output is cleared first (its blocks no product reaches stay zero).
 acse_status so_contract(acse_ctx c, SoWs &w, int n, double *out, const char *lo, const double *A, const char *la,
-                        const double *B, const char *lb, double alpha, int acc = 0) {
+                        int pa, const double *B, const char *lb, int pb, double alpha, int acc = 0) {
   auto pos = [](const char *t, char ch) {
     for (int k = 0; k < 4; ++k)
       if (t[k] == ch) return k;
     return -1;
   };
-  const int64_t n2 = (int64_t)n * n;
+  const int r = n / 2;
+  const int64_t n2 = (int64_t)n * n, r2 = (int64_t)r * r;
   const int64_t pw[4] = {n2 * n, n2, n, 1};
-  char fa[2], fb[2], kc[2];
+  char fa[2], fb[2], kl[2];
   int nfa = 0, nfb = 0, nk = 0;
   for (int k = 0; k < 4; ++k) {
     const char ch = lo[k];
@@ -1553,29 +1577,73 @@ acse_status so_contract(acse_ctx c, SoWs &w, int n, double *out, const char *lo,
     const char ch = la[k];
     if (pos(lo, ch) >= 0) continue;
     if (pos(lb, ch) < 0 || nk == 2) return fail(c, ACSE_ERR_HIP, "internal: bad spin-orbital contraction");
-    kc[nk++] = ch;
+    kl[nk++] = ch;
   }
   if (nfa != 2 || nfb != 2 || nk != 2) return fail(c, ACSE_ERR_HIP, "internal: bad spin-orbital contraction");
   hipStream_t s = c->stream;
-  const int64_t rows = op_rows(n), ld = op_ld(n);
-  auto relayout = [&](const double *src, const char *ls, const char *f, double *dst) {
-    PermArgs a{};
-    a.r = n; a.rows = rows; a.ld = ld; a.src1 = src; a.c1 = 1.0;
-    const char order[4] = {f[0], f[1], kc[0], kc[1]};
-    for (int k = 0; k < 4; ++k) a.s1[k] = pw[pos(ls, order[k])];
-    return launch_permute4(GEMM_F64, a, OperandRef{dst, nullptr}, s);
+  const int64_t rpad = so_rpad(r), kc = so_kc(r), ld = 4 * kc;
+  if (w.op_r != r) {
+    HIP_TRY(c, launch_fill(so_op_doubles(r), 0.0, w.opA, s));
+    HIP_TRY(c, launch_fill(so_op_doubles(r), 0.0, w.opB, s));
+    w.op_r = r;
+  }
+  auto pack = [&](const double *src, const char *ls, const char *f, int pair, double *dst) {
+    const char order[4] = {f[0], f[1], kl[0], kl[1]};
+    int64_t st[4];
+    int sp[4];
+    for (int k = 0; k < 4; ++k) {
+      sp[k] = pos(ls, order[k]);
+      st[k] = pw[sp[k]];
+    }
+    return launch_so_pack(r, rpad, kc, src, st, sp, pair, dst, s);
   };
-  HIP_TRY(c, relayout(A, la, fa, w.opA));
-  HIP_TRY(c, relayout(B, lb, fb, w.opB));
-  GemmBatch b{};
-  b.count = 1;
-  GemmProb &P = b.p[0];
-  P.A = w.opA; P.B = w.opB; P.C = out; P.alpha = alpha;
-  P.M = (int)n2; P.N = (int)n2; P.ld = (int)ld; P.Kp = gemm_kp(GEMM_F64, (int)n2, (int)ld); P.rdiv = n;
-  P.sm1 = pw[pos(lo, fa[0])]; P.sm0 = pw[pos(lo, fa[1])]; P.sn1 = pw[pos(lo, fb[0])]; P.sn0 = pw[pos(lo, fb[1])];
-  P.ksplit = 1; P.kchunk = P.Kp; P.accumulate = acc;
+  HIP_TRY(c, pack(A, la, fa, pa, w.opA));
+  HIP_TRY(c, pack(B, lb, fb, pb, w.opB));
+  if (!acc) HIP_TRY(c, launch_fill(n2 * n2, 0.0, out, s));
+  // spin of each source position for a (free-pair, summed-pair) block
+  auto nz = [&](const char *ls, const char *f, int pair, int RS, int KS) {
+    int sp[4];
+    sp[pos(ls, f[0])] = RS >> 1;
+    sp[pos(ls, f[1])] = RS & 1;
+    sp[pos(ls, kl[0])] = KS >> 1;
+    sp[pos(ls, kl[1])] = KS & 1;
+    return so_block_nonzero(pair, sp);
+  };
+  int ks[4][4][4], cnt[4][4] = {};
+  for (int RS = 0; RS < 4; ++RS)
+    for (int CS = 0; CS < 4; ++CS)
+      for (int KS = 0; KS < 4; ++KS)
+        if (nz(la, fa, pa, RS, KS) && nz(lb, fb, pb, CS, KS)) ks[RS][CS][cnt[RS][CS]++] = KS;
+  const int cfg = gemm_default_cfg(GEMM_F64, (int)r2, (int)r2);
+  const int kp = gemm_kp(GEMM_F64, (int)r2, (int)kc);
+  const int64_t sm1 = pw[pos(lo, fa[0])], sm0 = pw[pos(lo, fa[1])];
+  const int64_t sn1 = pw[pos(lo, fb[0])], sn0 = pw[pos(lo, fb[1])];
   StageTimer t7(c, 7);  // the products alone
-  HIP_TRY(c, gemm_launch(GEMM_F64, gemm_default_cfg(GEMM_F64, (int)n2, (int)n2), b, s));
+  // round t: the t-th summed spin pair of every output block (distinct outputs per launch)
+  for (int t = 0; t < 4; ++t) {
+    GemmBatch b{};
+    b.count = 0;
+    for (int RS = 0; RS < 4; ++RS)
+      for (int CS = 0; CS < 4; ++CS) {
+        if (cnt[RS][CS] <= t) continue;
+        const int KS = ks[RS][CS][t];
+        GemmProb &P = b.p[b.count++];
+        P = GemmProb{};
+        P.A = w.opA + RS * rpad * ld + KS * kc;
+        P.B = w.opB + CS * rpad * ld + KS * kc;
+        P.C = out + (RS >> 1) * r * sm1 + (RS & 1) * r * sm0 + (CS >> 1) * r * sn1 + (CS & 1) * r * sn0;
+        P.alpha = alpha;
+        P.M = (int)r2; P.N = (int)r2; P.ld = (int)ld; P.Kp = kp; P.rdiv = r;
+        P.sm1 = sm1; P.sm0 = sm0; P.sn1 = sn1; P.sn0 = sn0;
+        P.ksplit = 1; P.kchunk = kp; P.accumulate = (t == 0 && !acc) ? 0 : 1;
+        if (b.count == kMaxGemmProbs) {
+          HIP_TRY(c, gemm_launch(GEMM_F64, cfg, b, s));
+          b = GemmBatch{};
+          b.count = 0;
+        }
+      }
+    if (b.count) HIP_TRY(c, gemm_launch(GEMM_F64, cfg, b, s));
+  }
   return ACSE_OK;
 }
 
@@ -1613,10 +1681,10 @@ acse_status ny_vjp_share_run(acse_ctx c, const acse_problem *p, const double *Aa
   // forward: X, the cumulants, the three first-stage intermediates, Y
   HIP_TRY(c, launch_so_embed_singlet_x(r, Aaa, Aab, X, s));
   HIP_TRY(c, launch_so_cumulant(r, p->d1, p->d1, p->d2aa, p->d2aa, p->d2ab, w.sig, C2, CS, s));
-  if ((st = so_contract(c, w, n, W1, "kpia", X, "kprq", C2, "iarq", 1.0)) != ACSE_OK) return st;
+  if ((st = so_contract(c, w, n, W1, "kpia", X, "kprq", 1, C2, "iarq", 1, 1.0)) != ACSE_OK) return st;
   HIP_TRY(c, launch_so_trace_y(n, W1, w.Y, s));
-  if ((st = so_contract(c, w, n, M2, "kqja", X, "kprq", CS, "jpar", 1.0)) != ACSE_OK) return st;
-  if ((st = so_contract(c, w, n, M3, "kral", X, "kprq", C2, "palq", 1.0)) != ACSE_OK) return st;
+  if ((st = so_contract(c, w, n, M2, "kqja", X, "kprq", 1, CS, "jpar", 1, 1.0)) != ACSE_OK) return st;
+  if ((st = so_contract(c, w, n, M3, "kral", X, "kprq", 1, C2, "palq", 1, 1.0)) != ACSE_OK) return st;
   // cotangent of B; Tb = sw(Bbar), the cotangent shape of the sw() terms
   HIP_TRY(c, launch_so_bbar(r, Rbar_aa, Rbar_ab, 1.0, Bb, s));
   {
@@ -1627,23 +1695,23 @@ acse_status ny_vjp_share_run(acse_ctx c, const acse_problem *p, const double *Aa
     HIP_TRY(c, launch_combine4(n, Q, Tb, 0, nullptr, s));
   }
   // t_il (weight 4 on sw) and t_pl (weight 4, through Y)
-  if ((st = so_contract(c, w, n, Wb, "kpia", Tb, "ijkl", CS, "jpal", 4.0)) != ACSE_OK) return st;
+  if ((st = so_contract(c, w, n, Wb, "kpia", Tb, "ijkl", 1, CS, "jpal", 1, 4.0)) != ACSE_OK) return st;
   HIP_TRY(c, launch_so_ybar(n, 4.0, Bb, CS, w.Yb, s));
   HIP_TRY(c, launch_so_diag_add(n, w.Yb, Wb, s));
-  if ((st = so_contract(c, w, n, CSb, "jpal", Tb, "ijkl", W1, "kpia", 4.0)) != ACSE_OK) return st;
+  if ((st = so_contract(c, w, n, CSb, "jpal", Tb, "ijkl", 1, W1, "kpia", 1, 4.0)) != ACSE_OK) return st;
   HIP_TRY(c, launch_so_csbar_pl(n, 4.0, Bb, w.Y, CSb, s));
-  if ((st = so_contract(c, w, n, Xb, "kprq", Wb, "kpia", C2, "iarq", 1.0)) != ACSE_OK) return st;
-  if ((st = so_contract(c, w, n, C2b, "iarq", Wb, "kpia", X, "kprq", 1.0)) != ACSE_OK) return st;
+  if ((st = so_contract(c, w, n, Xb, "kprq", Wb, "kpia", 1, C2, "iarq", 1, 1.0)) != ACSE_OK) return st;
+  if ((st = so_contract(c, w, n, C2b, "iarq", Wb, "kpia", 1, X, "kprq", 1, 1.0)) != ACSE_OK) return st;
   // t_ir (weight -8 on sw)
-  if ((st = so_contract(c, w, n, Wb, "kqja", Tb, "ijkl", C2, "ialq", -8.0)) != ACSE_OK) return st;
-  if ((st = so_contract(c, w, n, C2b, "ialq", Tb, "ijkl", M2, "kqja", -8.0, 1)) != ACSE_OK) return st;
-  if ((st = so_contract(c, w, n, Xb, "kprq", Wb, "kqja", CS, "jpar", 1.0, 1)) != ACSE_OK) return st;
-  if ((st = so_contract(c, w, n, CSb, "jpar", Wb, "kqja", X, "kprq", 1.0, 1)) != ACSE_OK) return st;
+  if ((st = so_contract(c, w, n, Wb, "kqja", Tb, "ijkl", 1, C2, "ialq", 1, -8.0)) != ACSE_OK) return st;
+  if ((st = so_contract(c, w, n, C2b, "ialq", Tb, "ijkl", 1, M2, "kqja", 3, -8.0, 1)) != ACSE_OK) return st;
+  if ((st = so_contract(c, w, n, Xb, "kprq", Wb, "kqja", 3, CS, "jpar", 1, 1.0, 1)) != ACSE_OK) return st;
+  if ((st = so_contract(c, w, n, CSb, "jpar", Wb, "kqja", 3, X, "kprq", 1, 1.0, 1)) != ACSE_OK) return st;
   // t_pr (weight -8)
-  if ((st = so_contract(c, w, n, Wb, "kral", Bb, "ijkl", CS, "ijar", -8.0)) != ACSE_OK) return st;
-  if ((st = so_contract(c, w, n, CSb, "ijar", Bb, "ijkl", M3, "kral", -8.0, 1)) != ACSE_OK) return st;
-  if ((st = so_contract(c, w, n, Xb, "kprq", Wb, "kral", C2, "palq", 1.0, 1)) != ACSE_OK) return st;
-  if ((st = so_contract(c, w, n, C2b, "palq", Wb, "kral", X, "kprq", 1.0, 1)) != ACSE_OK) return st;
+  if ((st = so_contract(c, w, n, Wb, "kral", Bb, "ijkl", 1, CS, "ijar", 1, -8.0)) != ACSE_OK) return st;
+  if ((st = so_contract(c, w, n, CSb, "ijar", Bb, "ijkl", 1, M3, "kral", 3, -8.0, 1)) != ACSE_OK) return st;
+  if ((st = so_contract(c, w, n, Xb, "kprq", Wb, "kral", 3, C2, "palq", 1, 1.0, 1)) != ACSE_OK) return st;
+  if ((st = so_contract(c, w, n, C2b, "palq", Wb, "kral", 3, X, "kprq", 1, 1.0, 1)) != ACSE_OK) return st;
   // cs = sigma_a c2, c2 = 2D - (1D^1D)/2, then the singlet lifts
   HIP_TRY(c, launch_so_sigma_fold(n, w.sig, CSb, C2b, s));
   HIP_TRY(c, launch_so_d1bar_singlet(r, p->d1, C2b, gbar, s));
@@ -3219,9 +3287,9 @@ acse_status ny_spin_share(acse_ctx c, SpinWs &sw, const acse_problem_spin *p, co
   for (int b : kSix) HIP_TRY(c, launch_so_embed(r, b, sw.XA[b], 1.0, X, s));
   HIP_TRY(c, launch_so_cumulant(r, ga, gb, p->d2aa, p->d2bb, p->d2ab, w.sig, C2, CS, s));
   // x = i, y = l; then the p, l term through Y
-  if ((st = so_contract(c, w, n, W, "kpia", X, "kprq", C2, "iarq", 1.0)) != ACSE_OK) return st;
+  if ((st = so_contract(c, w, n, W, "kpia", X, "kprq", 1, C2, "iarq", 1, 1.0)) != ACSE_OK) return st;
   HIP_TRY(c, launch_so_trace_y(n, W, w.Y, s));
-  if ((st = so_contract(c, w, n, T, "ijkl", W, "kpia", CS, "jpal", 1.0)) != ACSE_OK) return st;
+  if ((st = so_contract(c, w, n, T, "ijkl", W, "kpia", 1, CS, "jpal", 1, 1.0)) != ACSE_OK) return st;
   {
     Terms4 Q{};
     Q.n = 2;
@@ -3231,8 +3299,8 @@ acse_status ny_spin_share(acse_ctx c, SpinWs &sw, const acse_problem_spin *p, co
   }
   HIP_TRY(c, launch_so_tpl(n, 4.0, w.Y, CS, B, s));
   // x = i, y = r (the y = q products equal these)
-  if ((st = so_contract(c, w, n, W, "kqja", X, "kprq", CS, "jpar", 1.0)) != ACSE_OK) return st;
-  if ((st = so_contract(c, w, n, T, "ijkl", W, "kqja", C2, "ialq", 1.0)) != ACSE_OK) return st;
+  if ((st = so_contract(c, w, n, W, "kqja", X, "kprq", 1, CS, "jpar", 1, 1.0)) != ACSE_OK) return st;
+  if ((st = so_contract(c, w, n, T, "ijkl", W, "kqja", 3, C2, "ialq", 1, 1.0)) != ACSE_OK) return st;
   {
     Terms4 Q{};
     Q.n = 2;
@@ -3241,8 +3309,8 @@ acse_status ny_spin_share(acse_ctx c, SpinWs &sw, const acse_problem_spin *p, co
     HIP_TRY(c, launch_combine4(n, Q, B, 1, nullptr, s));
   }
   // x = p, y = r: accumulated straight into B
-  if ((st = so_contract(c, w, n, W, "kral", X, "kprq", C2, "palq", 1.0)) != ACSE_OK) return st;
-  if ((st = so_contract(c, w, n, B, "ijkl", W, "kral", CS, "ijar", -8.0, 1)) != ACSE_OK) return st;
+  if ((st = so_contract(c, w, n, W, "kral", X, "kprq", 1, C2, "palq", 1, 1.0)) != ACSE_OK) return st;
+  if ((st = so_contract(c, w, n, B, "ijkl", W, "kral", 3, CS, "ijar", 1, -8.0, 1)) != ACSE_OK) return st;
   // S_b -= B_b - B_b(k<->l) on the spin block b of B
   for (int b : {B0000, B1111, B0101}) {
     const int64_t o0 = ((b >> 3) & 1) * (int64_t)r * n3, o1 = ((b >> 2) & 1) * (int64_t)r * n2;

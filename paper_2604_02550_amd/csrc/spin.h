@@ -69,6 +69,18 @@ hipError_t launch_so_trace_y(int n, const double *W, double *Y, hipStream_t s);
 // B[i,j,k,l] += c sum_a Y[k,a] cs[i,j,a,l].
 hipError_t launch_so_tpl(int n, double c, const double *Y, const double *cs, double *B, hipStream_t s);
 
+// Spin-blocked GEMM operand from a natural n^4 array (n = 2r): operand
+// position t reads the source with stride st[t]; the element with letter
+// values (L0, L1, L2, L3) (spin s_t = L_t >= r, spatial l_t = L_t - s_t r) goes
+// to row (2 s0 + s1) rpad + l0 r + l1, column (2 s2 + s3) kc + l2 r + l3 of a
+// row-major buffer with ld = 4 kc.  Only the r^2 x r^2 part of each block is
+// written (the padding is left as it is), and of it only the elements whose
+// source element conserves spin: src_pos[t] is the source position operand
+// position t reads, pair the source's conservation pair (spins of source
+// positions {0, pair} against the other two); the other blocks are never read.
+hipError_t launch_so_pack(int r, int64_t rpad, int64_t kc, const double *src, const int64_t st[4],
+                          const int src_pos[4], int pair, double *out, hipStream_t s);
+
 // ---- the NY share's adjoint on singlet states (spin-orbital, n = 2r) ---------
 // X (all n^4 elements) from the fold's blocks: same-spin blocks Aaa, the
 // (ab|ab) and (ba|ba) blocks Aab, the (ab|ba) and (ba|ab) blocks -Aab with the

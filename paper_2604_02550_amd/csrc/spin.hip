@@ -203,17 +203,90 @@ __global__ void __launch_bounds__(256) k_so_trace_y(int n, const double *__restr
 }
 
 // One thread per output element (i,j,k,l), the sum over a in a fixed order.
+// Y and cs conserve spin (Y_ka is zero unless a has the spin of k), so only
+// the spin-conserving outputs receive a contribution, and a runs over the
+// spin orbitals of k's spin.
 __global__ void __launch_bounds__(256)
 k_so_tpl(int n, double c, const double *__restrict__ Y, const double *__restrict__ cs, double *__restrict__ B) {
   const int64_t n2 = (int64_t)n * n;
   const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
   if (e >= n2 * n2) return;
-  const int l = (int)(e % n), k = (int)((e / n) % n);
+  const int r = n / 2;
+  const int l = (int)(e % n), k = (int)((e / n) % n), j = (int)((e / n2) % n), i = (int)(e / (n2 * n));
+  if ((i >= r) + (j >= r) != (k >= r) + (l >= r)) return;
   const int64_t ij = e / n2;
+  const int a0 = k >= r ? r : 0;
   const double *y = Y + (int64_t)k * n, *q = cs + ij * n2 + l;
   double acc = 0.0;
-  for (int a = 0; a < n; ++a) acc += y[a] * q[(int64_t)a * n];
+  for (int a = a0; a < a0 + r; ++a) acc += y[a] * q[(int64_t)a * n];
   B[e] += c * acc;
+}
+
+// One workgroup per (letter values of the two positions other than u and 3,
+// 32 x 32 tile over positions u and 3), u the operand position the source
+// reads with unit stride: the tile is read along u and written along position
+// 3 through LDS.  If the source's unit stride is position 3 itself (u = 3),
+// the tile is read and written along position 3 directly.
+struct SoPackArgs {
+  int64_t st[4];
+  int u, v, w;  // u: the unit-stride position (3: none other); v, w: the fixed ones
+  int src_pos[4];  // source position of each operand position
+  int pair;        // the source's conservation pair (with position 0)
+};
+// Whether the source element behind operand letter values L conserves spin.
+__device__ inline bool so_pack_keep(const SoPackArgs &a, int r, const int L[4]) {
+  int sp[4];
+  for (int t = 0; t < 4; ++t) sp[a.src_pos[t]] = L[t] >= r;
+  int o0 = 0, o1 = 0, k = 0;
+  for (int t = 1; t < 4; ++t)
+    if (t != a.pair) { if (k++ == 0) o0 = t; else o1 = t; }
+  return sp[0] + sp[a.pair] == sp[o0] + sp[o1];
+}
+__global__ void __launch_bounds__(256)
+k_so_pack(int r, int64_t rpad, int64_t kc, const double *__restrict__ src, SoPackArgs a, double *__restrict__ out) {
+  __shared__ double tile[32][33];
+  const int n = 2 * r;
+  const int nt = (n + 31) / 32;
+  const int64_t ld = 4 * kc;
+  int bid = blockIdx.x;
+  const int tu = bid % nt; bid /= nt;
+  const int t3 = bid % nt; bid /= nt;
+  const int Lw = bid % n, Lv = bid / n;
+  auto oaddr = [&](const int L[4]) {
+    const int s0 = L[0] >= r, s1 = L[1] >= r, s2 = L[2] >= r, s3 = L[3] >= r;
+    return ((int64_t)(2 * s0 + s1) * rpad + (int64_t)(L[0] - s0 * r) * r + (L[1] - s1 * r)) * ld +
+           (int64_t)(2 * s2 + s3) * kc + (int64_t)(L[2] - s2 * r) * r + (L[3] - s3 * r);
+  };
+  auto saddr = [&](const int L[4]) {
+    return L[0] * a.st[0] + L[1] * a.st[1] + L[2] * a.st[2] + L[3] * a.st[3];
+  };
+  if (a.u == 3) {
+    // positions v, w fixed by the block, tu indexes the third free position
+    // (stored in a.w's slot order: v, w, then the remaining one), t3 position 3
+    for (int q = threadIdx.x; q < 32 * 32; q += 256) {
+      const int i3 = q % 32, iu = q / 32;
+      int L[4];
+      L[a.v] = Lv; L[a.w] = Lw;
+      const int third = 3 - a.v - a.w;  // the position among 0..2 not v, w
+      L[third] = tu * 32 + iu;
+      L[3] = t3 * 32 + i3;
+      if (L[third] < n && L[3] < n && so_pack_keep(a, r, L)) out[oaddr(L)] = src[saddr(L)];
+    }
+    return;
+  }
+  for (int q = threadIdx.x; q < 32 * 32; q += 256) {
+    const int iu = q % 32, i3 = q / 32;
+    int L[4];
+    L[a.v] = Lv; L[a.w] = Lw; L[a.u] = tu * 32 + iu; L[3] = t3 * 32 + i3;
+    tile[i3][iu] = (L[a.u] < n && L[3] < n && so_pack_keep(a, r, L)) ? src[saddr(L)] : 0.0;
+  }
+  __syncthreads();
+  for (int q = threadIdx.x; q < 32 * 32; q += 256) {
+    const int i3 = q % 32, iu = q / 32;
+    int L[4];
+    L[a.v] = Lv; L[a.w] = Lw; L[a.u] = tu * 32 + iu; L[3] = t3 * 32 + i3;
+    if (L[a.u] < n && L[3] < n && so_pack_keep(a, r, L)) out[oaddr(L)] = tile[i3][iu];
+  }
 }
 
 // ---- adjoint of the NY share on singlet states ------------------------------
@@ -281,23 +354,53 @@ k_so_bbar(int r, const double *__restrict__ Raa, const double *__restrict__ Rab,
   Bb[e] = -rb(I, J, K, L) + rb(I, J, L, K) + sign * (rb(K, L, I, J) - rb(L, K, I, J));
 }
 
-// One workgroup of 256 per (k, a); the threads stride over (i, j, l) with l
-// fastest, then a fixed-order reduction.
+// One workgroup of 256 per (k, a-tile of 8 spin orbitals of k's spin): the
+// threads stride over the (i, j, l) that conserve spin with k (l fastest),
+// each B element read once for the eight a; fixed-order reductions.  Bbar
+// and cs conserve spin, so Ybar vanishes unless a has the spin of k.
 __global__ void __launch_bounds__(256)
 k_so_ybar(int n, double c, const double *__restrict__ Bb, const double *__restrict__ cs, double *__restrict__ Yb) {
-  __shared__ double part[4];
-  const int k = blockIdx.x / n, a = blockIdx.x % n;
-  const int64_t n2 = (int64_t)n * n, tot = n2 * n;
-  double acc = 0.0;
-  for (int64_t e = threadIdx.x; e < tot; e += 256) {
-    const int64_t ij = e / n;
-    const int l = (int)(e - ij * n);
-    acc += Bb[ij * n2 + (int64_t)k * n + l] * cs[ij * n2 + (int64_t)a * n + l];
+  constexpr int TA = 8;
+  __shared__ double part[4][TA];
+  const int r = n / 2, at = (r + TA - 1) / TA;
+  const int k = blockIdx.x / (2 * at), rest = blockIdx.x % (2 * at);
+  const int sa = rest / at, a0 = (rest % at) * TA;  // a = sa r + a0 + t
+  const int sk = k >= r;
+  const int64_t n2 = (int64_t)n * n;
+  if (sa != sk) {  // zero
+    if (threadIdx.x < TA && a0 + (int)threadIdx.x < r) Yb[(int64_t)k * n + sa * r + a0 + threadIdx.x] = 0.0;
+    return;
   }
-  for (int off = 32; off > 0; off >>= 1) acc += __shfl_down(acc, off, 64);
-  if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = acc;
+  double acc[TA];
+  for (int t = 0; t < TA; ++t) acc[t] = 0.0;
+  // (s_i, s_j, s_l) with s_i + s_j = s_k + s_l: for each of the two s_l, the
+  // (s_i, s_j) pairs with that sum; flattened over (i, j, l) of the spin case
+  for (int sl = 0; sl < 2; ++sl) {
+    const int tot_s = sk + sl;
+    for (int si = 0; si < 2; ++si) {
+      const int sj = tot_s - si;
+      if (sj < 0 || sj > 1) continue;
+      const int64_t cnt = (int64_t)r * r * r;
+      for (int64_t e = threadIdx.x; e < cnt; e += 256) {
+        const int l = (int)(e % r), j = (int)((e / r) % r), i = (int)(e / ((int64_t)r * r));
+        const int64_t ij = (int64_t)(i + si * r) * n + (j + sj * r);
+        const double bv = Bb[ij * n2 + (int64_t)k * n + l + sl * r];
+        const double *q = cs + ij * n2 + (int64_t)(sa * r + a0) * n + l + sl * r;
+        for (int t = 0; t < TA; ++t)
+          if (a0 + t < r) acc[t] += bv * q[(int64_t)t * n];
+      }
+    }
+  }
+  for (int t = 0; t < TA; ++t) {
+    double v = acc[t];
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+    if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6][t] = v;
+  }
   __syncthreads();
-  if (threadIdx.x == 0) Yb[blockIdx.x] = c * (((part[0] + part[1]) + part[2]) + part[3]);
+  if (threadIdx.x < TA && a0 + (int)threadIdx.x < r) {
+    const int t = threadIdx.x;
+    Yb[(int64_t)k * n + sa * r + a0 + t] = c * (((part[0][t] + part[1][t]) + part[2][t]) + part[3][t]);
+  }
 }
 
 __global__ void __launch_bounds__(256)
@@ -305,11 +408,16 @@ k_so_csbar_pl(int n, double c, const double *__restrict__ Bb, const double *__re
   const int64_t n2 = (int64_t)n * n;
   const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
   if (e >= n2 * n2) return;
-  const int l = (int)(e % n), a = (int)((e / n) % n);
+  const int r = n / 2;
+  const int l = (int)(e % n), a = (int)((e / n) % n), j = (int)((e / n2) % n), i = (int)(e / (n2 * n));
+  // Bbar and Y conserve spin: only conserving (i,j,a,l) receive a
+  // contribution, and k runs over the spin orbitals of a's spin
+  if ((i >= r) + (j >= r) != (a >= r) + (l >= r)) return;
   const int64_t ij = e / n2;
+  const int k0 = a >= r ? r : 0;
   const double *b = Bb + ij * n2 + l;
   double acc = 0.0;
-  for (int k = 0; k < n; ++k) acc += b[(int64_t)k * n] * Y[(int64_t)k * n + a];
+  for (int k = k0; k < k0 + r; ++k) acc += b[(int64_t)k * n] * Y[(int64_t)k * n + a];
   CSb[e] += c * acc;
 }
 
@@ -328,29 +436,29 @@ k_so_sigma_fold(int n, const double *__restrict__ sig, const double *__restrict_
   C2b[e] += sig[(e / n) % n] * CSb[e];
 }
 
-// One thread per spatial (x, y): both spin blocks of the output, each sum over
-// the nonzero (same-spin) entries of D1 = diag(g, g).
+// One workgroup of 256 per spatial (x, y): both spin blocks of the output,
+// each a sum over the nonzero (same-spin) entries of D1 = diag(g, g), the
+// threads striding over (spin of J, j, q); fixed-order reduction.
 __global__ void __launch_bounds__(256)
 k_so_d1bar_singlet(int r, const double *__restrict__ g, const double *__restrict__ cb, double *__restrict__ gb) {
-  const int e = blockIdx.x * 256 + threadIdx.x;
-  if (e >= r * r) return;
-  const int x = e / r, y = e % r;
+  __shared__ double part[4];
+  const int x = blockIdx.x / r, y = blockIdx.x % r;
   const int64_t n = 2 * (int64_t)r;
   auto at = [&](int64_t a, int64_t b, int64_t c, int64_t d) { return cb[((a * n + b) * n + c) * n + d]; };
-  double tot = 0.0;
+  double acc = 0.0;
+  const int64_t per = 2 * (int64_t)r * r;  // (spin of J, j, q)
   for (int sx = 0; sx < 2; ++sx) {
     const int64_t X = x + sx * r, Y = y + sx * r;
-    double acc = 0.0;
-    for (int sj = 0; sj < 2; ++sj)
-      for (int j = 0; j < r; ++j)
-        for (int q = 0; q < r; ++q) {
-          const double d = g[j * r + q];
-          const int64_t J = j + sj * r, Q = q + sj * r;
-          acc += d * (at(X, J, Y, Q) + at(J, X, Q, Y) - at(J, X, Y, Q) - at(X, J, Q, Y));
-        }
-    tot += -0.5 * acc;
+    for (int64_t e = threadIdx.x; e < per; e += 256) {
+      const int q = (int)(e % r), j = (int)((e / r) % r), sj = (int)(e / ((int64_t)r * r));
+      const int64_t J = j + sj * r, Q = q + sj * r;
+      acc += g[j * r + q] * (at(X, J, Y, Q) + at(J, X, Q, Y) - at(J, X, Y, Q) - at(X, J, Q, Y));
+    }
   }
-  gb[e] += tot;
+  for (int off = 32; off > 0; off >>= 1) acc += __shfl_down(acc, off, 64);
+  if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = acc;
+  __syncthreads();
+  if (threadIdx.x == 0) gb[blockIdx.x] += -0.5 * (((part[0] + part[1]) + part[2]) + part[3]);
 }
 
 inline dim3 grid1(int64_t n) { return dim3((unsigned)((n + 255) / 256)); }
@@ -425,6 +533,26 @@ hipError_t launch_so_tpl(int n, double c, const double *Y, const double *cs, dou
   return hipGetLastError();
 }
 
+hipError_t launch_so_pack(int r, int64_t rpad, int64_t kc, const double *src, const int64_t st[4],
+                          const int src_pos[4], int pair, double *out, hipStream_t s) {
+  SoPackArgs a{};
+  for (int t = 0; t < 4; ++t) {
+    a.st[t] = st[t];
+    a.src_pos[t] = src_pos[t];
+  }
+  a.pair = pair;
+  a.u = 3;
+  for (int t = 0; t < 3; ++t)
+    if (st[t] == 1) a.u = t;
+  // the fixed positions: the two of 0..2 other than u (for u = 3: positions 0 and 1)
+  if (a.u == 3) { a.v = 0; a.w = 1; }
+  else { a.v = a.u == 0 ? 1 : 0; a.w = a.u == 2 ? 1 : 2; }
+  const int n = 2 * r, nt = (n + 31) / 32;
+  hipLaunchKernelGGL(k_so_pack, dim3((unsigned)((int64_t)n * n * nt * nt)), dim3(256), 0, s, r, rpad, kc, src, a,
+                     out);
+  return hipGetLastError();
+}
+
 hipError_t launch_so_embed_singlet_x(int r, const double *Aaa, const double *Aab, double *X, hipStream_t s) {
   const int64_t n = 2 * (int64_t)r;
   hipLaunchKernelGGL(k_so_embed_singlet_x, grid1(n * n * n * n), dim3(256), 0, s, r, Aaa, Aab, X);
@@ -449,7 +577,8 @@ hipError_t launch_so_bbar(int r, const double *Rbar_aa, const double *Rbar_ab, d
 }
 
 hipError_t launch_so_ybar(int n, double c, const double *Bbar, const double *cs, double *Ybar, hipStream_t s) {
-  hipLaunchKernelGGL(k_so_ybar, dim3((unsigned)(n * n)), dim3(256), 0, s, n, c, Bbar, cs, Ybar);
+  const int r = n / 2;
+  hipLaunchKernelGGL(k_so_ybar, dim3((unsigned)(n * 2 * ((r + 7) / 8))), dim3(256), 0, s, n, c, Bbar, cs, Ybar);
   return hipGetLastError();
 }
 
@@ -469,7 +598,7 @@ hipError_t launch_so_sigma_fold(int n, const double *sig, const double *CSbar, d
 }
 
 hipError_t launch_so_d1bar_singlet(int r, const double *g, const double *C2bar, double *gbar, hipStream_t s) {
-  hipLaunchKernelGGL(k_so_d1bar_singlet, grid1((int64_t)r * r), dim3(256), 0, s, r, g, C2bar, gbar);
+  hipLaunchKernelGGL(k_so_d1bar_singlet, dim3((unsigned)(r * r)), dim3(256), 0, s, r, g, C2bar, gbar);
   return hipGetLastError();
 }
 
