@@ -1772,6 +1772,25 @@ extern "C" acse_status acse_residual_vjp(acse_ctx ctx, const acse_problem *prob,
   };
   // natural r^4 destination
   auto natref = [&](double *p) { return OperandRef{p, nullptr}; };
+  // The backward pass queues its permutes and launches the queue in batches
+  // (launch_permute4_batch): before any other kernel, and before a permute
+  // that would write what a queued one reads or writes, or read what one writes.
+  PermArgs pq_a[kMaxPermJobs];
+  OperandRef pq_o[kMaxPermJobs];
+  GemmPrec pq_p[kMaxPermJobs];
+  int pq_n = 0;
+  auto flushq = [&]() -> hipError_t {
+    if (!pq_n) return hipSuccess;
+    const int n = pq_n;
+    pq_n = 0;
+    return launch_permute4_batch(pq_p, pq_a, pq_o, n, s);
+  };
+  const int64_t nat_bytes = r2 * r2 * 8;
+  auto overlap = [](const void *p, int64_t pb, const void *q, int64_t qb) {
+    if (!p || !q) return false;
+    const char *x = static_cast<const char *>(p), *y = static_cast<const char *>(q);
+    return x < y + qb && y < x + pb;
+  };
   auto permute = [&](GemmPrec pr, const OperandRef &dst, bool operand_layout, const double *s1,
                      const int m1[4], double c1, const double *s2, const int m2[4], double c2,
                      int acc) -> hipError_t {
@@ -1786,12 +1805,30 @@ extern "C" acse_status acse_residual_vjp(acse_ctx ctx, const acse_problem *prob,
     if (s2) nat.map(m2, a.s2);
     a.c2 = c2;
     a.accumulate = acc;
-    return launch_permute4(pr, a, dst, s);
+    const int64_t db = a.rows * a.ld * 8;
+    bool clash = pq_n == kMaxPermJobs;
+    for (int q = 0; q < pq_n && !clash; ++q) {
+      const int64_t qb = pq_a[q].rows * pq_a[q].ld * 8;
+      clash = overlap(dst.hi, db, pq_o[q].hi, qb) || overlap(dst.hi, db, pq_a[q].src1, nat_bytes) ||
+              overlap(dst.hi, db, pq_a[q].src2, nat_bytes) || overlap(s1, nat_bytes, pq_o[q].hi, qb) ||
+              overlap(s2, nat_bytes, pq_o[q].hi, qb);
+    }
+    if (clash) {
+      hipError_t e = flushq();
+      if (e != hipSuccess) return e;
+    }
+    pq_a[pq_n] = a;
+    pq_o[pq_n] = dst;
+    pq_p[pq_n] = pr;
+    ++pq_n;
+    return hipSuccess;
   };
   const int ID[4] = {0, 1, 2, 3};
   auto mode = [&](const double *in1, const double *in2, double c2, const double *M, int tr,
                   int64_t A, int64_t Bn, double alpha, double *out, int64_t adiv, int64_t so1,
                   int64_t so0, int64_t sx, int64_t sb, int cols_fast, int acc) -> hipError_t {
+    hipError_t fe = flushq();
+    if (fe != hipSuccess) return fe;
     ModeArgs m = mode_base(ctx, r, M);
     m.A = A; m.Bn = Bn; m.in1 = in1; m.in2 = in2; m.c2 = c2; m.transpose_m = tr;
     m.alpha = alpha; m.adiv = adiv; m.so1 = so1; m.so0 = so0; m.sx = sx; m.sb = sb;
@@ -1804,19 +1841,26 @@ extern "C" acse_status acse_residual_vjp(acse_ctx ctx, const acse_problem *prob,
     return t;
   };
   auto contract = [&](std::initializer_list<ContractTerm> terms, double *out, int acc) -> hipError_t {
+    hipError_t fe = flushq();
+    if (fe != hipSuccess) return fe;
     ContractArgs a{};
     for (const ContractTerm &t : terms) a.term[a.nterms++] = t;
     return launch_contract42(r, a, out, acc, w.tpart, s);
   };
 
   // ---------------- forward recompute (natural layouts) -------------------
+  HIP_TRY(ctx, flushq());
   if ((st = prep_rdm_operands(ctx, prob, prec)) != ACSE_OK) return st;
+  HIP_TRY(ctx, flushq());
   HIP_TRY(ctx, launch_fold(r, N, prob->h, prob->V, w.Aaa, w.Aab, s));
+  HIP_TRY(ctx, flushq());
   HIP_TRY(ctx, launch_f(r, w.Aaa, w.Aab, g, w.fpart, w.f, s));
+  HIP_TRY(ctx, flushq());
   HIP_TRY(ctx, launch_t(r, w.Waa, w.Aaa, w.Wab, w.Aab, w.tpart, w.t, s, ctx->general));
   for (int b = 0; b < 2; ++b)
     HIP_TRY(ctx, mode(b ? w.Aab : w.Aaa, nullptr, 0.0, g, 1, r, r2, 1.0, b ? w.Hab : w.Haa, 1, r3, 0,
                       r2, 1, 1, 0));
+  HIP_TRY(ctx, flushq());
   HIP_TRY(ctx, launch_g2(prec, r, ctx->general, w.Aaa, w.Aab, w.Haa, w.Hab, w.f, w.G2aa, w.G2ab, vop(0),
                          vop(1), vop(2), s));
   // B = A - G2, L+-, L3 and R+-, R3 are written straight into the GEMM operand
@@ -1828,7 +1872,9 @@ extern "C" acse_status acse_residual_vjp(acse_ctx ctx, const acse_problem *prob,
   double *Gbaa = V[19], *Gbab = V[20], *Bbaa = V[21], *Bbab = V[22], *Maa = V[23], *Mab = V[24];
   double *G2baa = V[25], *G2bab = V[26], *Abaa = V[27], *Abab = V[28], *Wbaa = V[29], *Wbab = V[30];
   double *T1 = V[31], *T2 = V[32], *T3 = V[33], *T4 = V[34], *Vraw = V[35];
+  HIP_TRY(ctx, flushq());
   HIP_TRY(ctx, launch_fill(r2, 0.0, gb, s));
+  HIP_TRY(ctx, flushq());
   HIP_TRY(ctx, launch_identity(r, Id, s));
   // S-bar = R-bar - R-bar^T  (R = S - S^T)
   {
@@ -1845,6 +1891,7 @@ extern "C" acse_status acse_residual_vjp(acse_ctx ctx, const acse_problem *prob,
                          term(Sbaa, 0, 2, 1, 3, w.t, 1.0), term(Sbaa, 1, 2, 0, 3, w.t, -1.0),
                          term(Sbab, 1, 3, 0, 2, w.t, 1.0), term(Sbab, 0, 2, 1, 3, w.t, 1.0)},
                         gb, 1));
+  HIP_TRY(ctx, flushq());
   HIP_TRY(ctx, launch_vjp_pe(r, Sbaa, Sbab, Ppb, Pmb, E3b, s));
 
   int kdim[kMaxGemmProbs] = {};  // K of each product of the batch being built
@@ -1874,7 +1921,9 @@ extern "C" acse_status acse_residual_vjp(acse_ctx ctx, const acse_problem *prob,
     return -1;
   };
   auto vjp_gemm = [&](GemmBatch &b) -> acse_status {
+    HIP_TRY(ctx, flushq());
     if (!crt) {
+      HIP_TRY(ctx, flushq());
       HIP_TRY(ctx, gemm_launch(prec, use_cfg, b, s));
       return ACSE_OK;
     }
@@ -1911,6 +1960,7 @@ extern "C" acse_status acse_residual_vjp(acse_ctx ctx, const acse_problem *prob,
       nrows += brows[q];
     }
     rb.total_rows = nrows;
+    HIP_TRY(ctx, flushq());
     HIP_TRY(ctx, launch_to_residues(rb, ctx->crt, s));
     int64_t yoff = 0;  // the products' residues one after another (their sizes differ)
     for (int k = 0; k < b.count; ++k) {
@@ -1930,6 +1980,7 @@ extern "C" acse_status acse_residual_vjp(acse_ctx ctx, const acse_problem *prob,
       G.Y = ctx->vcy + yoff;
       yoff += (int64_t)ctx->crt.nmod * G.plane_y;
     }
+    HIP_TRY(ctx, flushq());
     HIP_TRY(ctx, gemm_crt_launch(b, ctx->crt, s));
     HIP_TRY(ctx, crt_combine_launch(b, ctx->crt, s));
     return ACSE_OK;
@@ -1944,7 +1995,9 @@ extern "C" acse_status acse_residual_vjp(acse_ctx ctx, const acse_problem *prob,
     // as rows (p,s), cols (k,i): written by the mode products with operand strides
     auto lop = [&](int q, const double *in1, const double *in2, double c2, int64_t A, int64_t Bn,
                    int64_t adiv, int64_t so1, int64_t so0, int64_t sb) -> hipError_t {
-      hipError_t e = launch_zero_kpad(prec, r, ld, vop(q), s);
+      hipError_t e = flushq();
+      if (e != hipSuccess) return e;
+      e = launch_zero_kpad(prec, r, ld, vop(q), s);
       if (e != hipSuccess) return e;
       ModeArgs m = mode_base(ctx, r, g);
       m.A = A; m.Bn = Bn; m.in1 = in1; m.in2 = in2; m.c2 = c2;
@@ -1998,6 +2051,8 @@ extern "C" acse_status acse_residual_vjp(acse_ctx ctx, const acse_problem *prob,
     const int64_t ldlt = ld_pair_lt(r), ldle = ld_pair_le(r);
     struct PackTerm { const double *src; const int *map; double c; int offdiag; };
     auto pack = [&](int q, int rows_mode, int k_le, std::initializer_list<PackTerm> terms) -> hipError_t {
+      hipError_t fe = flushq();
+      if (fe != hipSuccess) return fe;
       PairPackArgs a{};
       a.r = r;
       a.rows_mode = rows_mode;
@@ -2073,8 +2128,11 @@ extern "C" acse_status acse_residual_vjp(acse_ctx ctx, const acse_problem *prob,
       gemm_set(b, 4, 7, 9, 4.0, Bbab, ID);   // 2 * Gamma2_ab = 4 d2ab
       gemm_set(b, 5, 6, 10, 1.0, Mab, ID);
       if ((st = vjp_gemm(b)) != ACSE_OK) return st;
+      HIP_TRY(ctx, flushq());
       HIP_TRY(ctx, launch_unpack_pairs(r, 1, T1, nlt, Gbaa, s));
+      HIP_TRY(ctx, flushq());
       HIP_TRY(ctx, launch_unpack_pairs(r, 0, T2, nlt, Bbaa, s));
+      HIP_TRY(ctx, flushq());
       HIP_TRY(ctx, launch_unpack_pairs(r, 0, T3, nlt, Maa, s));
     }
     if (pack_ab) {
@@ -2095,9 +2153,13 @@ extern "C" acse_status acse_residual_vjp(acse_ctx ctx, const acse_problem *prob,
       pair_set(b, 3, 6, 7, 2.0, Gp, nle, nle, 1);
       pair_set(b, 4, 8, 9, 2.0, Gm, nlt, nlt, 0);
       if ((st = vjp_gemm(b)) != ACSE_OK) return st;
+      HIP_TRY(ctx, flushq());
       HIP_TRY(ctx, launch_unpack_pairs(r, 1, T1, nlt, Gbaa, s));
+      HIP_TRY(ctx, flushq());
       HIP_TRY(ctx, launch_unpack_pairs(r, 0, T2, nlt, Bbaa, s));
+      HIP_TRY(ctx, flushq());
       HIP_TRY(ctx, launch_unpack_pairs(r, 0, T3, nlt, Maa, s));
+      HIP_TRY(ctx, flushq());
       HIP_TRY(ctx, launch_unpack_pm(r, 1, Gp, nle, Gm, nlt, Gbab, s));
     }
     if (pack_ab) {
@@ -2121,7 +2183,9 @@ extern "C" acse_status acse_residual_vjp(acse_ctx ctx, const acse_problem *prob,
       pair_set(b, 2, 4, 5, 1.0, Mp, R2, nle, 1);
       pair_set(b, 3, 6, 7, 1.0, Mm, R2, nlt, 0);
       if ((st = vjp_gemm(b)) != ACSE_OK) return st;
+      HIP_TRY(ctx, flushq());
       HIP_TRY(ctx, launch_unpack_pm(r, 0, Bp, nle, Bm, nlt, Bbab, s));
+      HIP_TRY(ctx, flushq());
       HIP_TRY(ctx, launch_unpack_pm(r, 0, Mp, nle, Mm, nlt, Mab, s));
     }
   }
@@ -2166,6 +2230,7 @@ extern "C" acse_status acse_residual_vjp(acse_ctx ctx, const acse_problem *prob,
     HIP_TRY(ctx, permute(GEMM_F64, natref(T2), false, Hbaa, lead1, 1.0, nullptr, ID, 0.0, 0));
     HIP_TRY(ctx, permute(GEMM_F64, natref(T3), false, w.Aab, lead1, 1.0, nullptr, ID, 0.0, 0));
     HIP_TRY(ctx, permute(GEMM_F64, natref(T4), false, Hbab, lead1, 1.0, nullptr, ID, 0.0, 0));
+    HIP_TRY(ctx, flushq());
     HIP_TRY(ctx, launch_gram(r, T1, T2, 1.0, T3, T4, 1.0, w.tpart, gb, 1, s, ctx->general));
   }
   // W-bar from the ph B operands
@@ -2182,6 +2247,7 @@ extern "C" acse_status acse_residual_vjp(acse_ctx ctx, const acse_problem *prob,
   HIP_TRY(ctx, mode(w.Waa, nullptr, 0.0, tb, 1, 1, r3, 1.0, Abaa, 1, 0, 0, r3, 1, 1, 1));
   HIP_TRY(ctx, mode(w.Wab, nullptr, 0.0, tb, 1, 1, r3, 2.0, Abab, 1, 0, 0, r3, 1, 1, 1));
   // f terms
+  HIP_TRY(ctx, flushq());
   HIP_TRY(ctx, launch_vjp_frank(r, fb, g, Abaa, Abab, s));
   HIP_TRY(ctx, contract({term(w.Aaa, 1, 2, 0, 3, fb, 1.0), term(w.Aab, 1, 3, 0, 2, fb, -1.0)}, gb, 1));
   // L terms: A-bar[k,p,r,s] += sum_i g[i,r] (L+b +- L-b)[k,i,p,s]; L3: A_ab-bar[k,p,s,r] += sum_j g[j,r] L3b[k,j,p,s]
@@ -2201,11 +2267,13 @@ extern "C" acse_status acse_residual_vjp(acse_ctx ctx, const acse_problem *prob,
     HIP_TRY(ctx, permute(GEMM_F64, natref(T2), false, w.Aaa, r_kps, 1.0, w.Aab, r_kps, 1.0, 0));
     HIP_TRY(ctx, permute(GEMM_F64, natref(T3), false, Lmb, i_kps, 1.0, nullptr, ID, 0.0, 0));
     HIP_TRY(ctx, permute(GEMM_F64, natref(T4), false, w.Aaa, r_kps, 1.0, w.Aab, r_kps, -1.0, 0));
+    HIP_TRY(ctx, flushq());
     HIP_TRY(ctx, launch_gram(r, T1, T2, 1.0, T3, T4, 1.0, w.tpart, gb, 1, s, ctx->general));
     // gamma-bar[j,r] += sum L3b[k,j,p,s] A_ab[k,p,s,r]
     const int r_kps3[4] = {3, 0, 1, 2};  // [r][k,p,s] from A_ab[k,p,s,r]
     HIP_TRY(ctx, permute(GEMM_F64, natref(T1), false, L3b, i_kps, 1.0, nullptr, ID, 0.0, 0));
     HIP_TRY(ctx, permute(GEMM_F64, natref(T2), false, w.Aab, r_kps3, 1.0, nullptr, ID, 0.0, 0));
+    HIP_TRY(ctx, flushq());
     HIP_TRY(ctx, launch_gram(r, T1, T2, 1.0, nullptr, nullptr, 0.0, w.tpart, gb, 1, s, ctx->general));
   }
   // W = Gamma2 - 2/3 g^g:  gamma-bar from W-bar
@@ -2214,19 +2282,27 @@ extern "C" acse_status acse_residual_vjp(acse_ctx ctx, const acse_problem *prob,
                          term(Wbab, 0, 2, 1, 3, g, -2.0 / 3.0), term(Wbab, 1, 3, 0, 2, g, -2.0 / 3.0)},
                         gb, 1));
   // the NY share's adjoint joins the accumulators before their projections
+  HIP_TRY(ctx, flushq());
   if (ctx->ny_on && (st = ny_vjp_share(ctx, prob, w.Aaa, w.Aab, Rbar_aa, Rbar_ab, Abaa, Abab, Gbaa, Gbab, gb)) !=
                         ACSE_OK)
     return st;
   // Gamma2-bar = G-bar (GEMM) + W-bar;  d2-bar = 2 Gamma2-bar (projected)
   HIP_TRY(ctx, permute(GEMM_F64, natref(Gbaa), false, Wbaa, ID, 1.0, nullptr, ID, 0.0, 1));
   HIP_TRY(ctx, permute(GEMM_F64, natref(Gbab), false, Wbab, ID, 1.0, nullptr, ID, 0.0, 1));
+  HIP_TRY(ctx, flushq());
   HIP_TRY(ctx, launch_proj(PROJ_AA, r, 2.0, Gbaa, d2aa_bar, s));
+  HIP_TRY(ctx, flushq());
   HIP_TRY(ctx, launch_proj(PROJ_AB, r, 2.0, Gbab, d2ab_bar, s));
+  HIP_TRY(ctx, flushq());
   HIP_TRY(ctx, launch_proj(PROJ_SYM2, r, 1.0, gb, d1_bar, s));
   // fold adjoint -> V-bar, h-bar
+  HIP_TRY(ctx, flushq());
   HIP_TRY(ctx, launch_vjp_fold(r, N, Abaa, Abab, Vraw, hb_raw, s));
+  HIP_TRY(ctx, flushq());
   HIP_TRY(ctx, launch_proj(PROJ_V, r, 1.0, Vraw, V_bar, s));
+  HIP_TRY(ctx, flushq());
   HIP_TRY(ctx, launch_proj(PROJ_SYM2, r, 1.0, hb_raw, h_bar, s));
+  HIP_TRY(ctx, flushq());
   return ACSE_OK;
 }
 

@@ -19,6 +19,13 @@ struct PermArgs {
   int accumulate;      // FP64 output only: dst += value (padding untouched)
 };
 hipError_t launch_permute4(GemmPrec prec, const PermArgs &a, const OperandRef &out, hipStream_t s);
+// Several permutes, each as launch_permute4 would run it, in as few launches
+// as their destination types allow (up to kMaxPermJobs a launch).  The jobs
+// must be independent: distinct destinations, and no job reads what another
+// writes.
+constexpr int kMaxPermJobs = 10;
+hipError_t launch_permute4_batch(const GemmPrec *prec, const PermArgs *a, const OperandRef *out, int count,
+                                 hipStream_t s);
 
 // out[x,y] (+)= sum_t c_t sum_{u,v} T_t[x sx + y sy + u su + v sv] M_t[u*r + v]
 struct ContractTerm {

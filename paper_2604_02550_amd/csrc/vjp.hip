@@ -39,10 +39,8 @@ struct VOutBF16x3 {
 constexpr int kPermU = 10;
 
 template <class O>
-__global__ void __launch_bounds__(256)
-k_permute4(PermArgs a, O out) {
+__device__ __forceinline__ void perm_row(const PermArgs &a, const O &out, int row) {
   const int r = a.r, r2 = r * r;
-  const int row = blockIdx.x;
   const int64_t o = (int64_t)row * a.ld;
   const int ld = (int)a.ld;
   if (row >= r2) {
@@ -75,6 +73,12 @@ k_permute4(PermArgs a, O out) {
   }
 }
 
+template <class O>
+__global__ void __launch_bounds__(256)
+k_permute4(PermArgs a, O out) {
+  perm_row(a, out, (int)blockIdx.x);
+}
+
 // The same permute when a source's unit-stride index is destination position
 // q < 3 (so the elementwise form reads it with a stride): one block per value
 // of the two other leading positions moves the r x r slice (position q,
@@ -89,11 +93,10 @@ struct SliceStrides {
 };
 
 template <class O>
-__global__ void __launch_bounds__(256)
-k_permute4_slice(PermArgs a, SliceStrides t, O out) {
-  extern __shared__ double ps_smem[];
+__device__ __forceinline__ void perm_slice(const PermArgs &a, const SliceStrides &t, const O &out, int bid,
+                                           double *ps_smem) {
   const int r = a.r, rp = r + 1;
-  const int x1 = blockIdx.x / r, x2 = blockIdx.x - (blockIdx.x / r) * r;
+  const int x1 = bid / r, x2 = bid - (bid / r) * r;
   const int64_t b1 = x1 * t.s1a + x2 * t.s1b;
   const int64_t b2 = a.src2 ? x1 * t.s2a + x2 * t.s2b : 0;
   const bool two = a.src2 != nullptr;
@@ -127,19 +130,67 @@ k_permute4_slice(PermArgs a, SliceStrides t, O out) {
   }
 }
 
+template <class O>
+__global__ void __launch_bounds__(256)
+k_permute4_slice(PermArgs a, SliceStrides t, O out) {
+  extern __shared__ double ps_smem[];
+  perm_slice(a, t, out, (int)blockIdx.x, ps_smem);
+}
+
 // zero padding of an operand-layout permute destination: rows >= r^2 and the
 // columns >= r^2 of the first r^2 rows
 template <class O>
-__global__ void k_permute4_pad(PermArgs a, O out) {
+__device__ __forceinline__ void perm_pad(const PermArgs &a, const O &out, int64_t e) {
   const int64_t r2 = (int64_t)a.r * a.r;
   const int64_t padc = a.ld - r2;
   const int64_t n1 = r2 * padc;  // column padding of the first r^2 rows
-  const int64_t e = vtid();
   if (e < n1) {
     out.put((e / padc) * a.ld + r2 + e % padc, 0.0);
   } else if (e - n1 < (a.rows - r2) * a.ld) {
     out.put(r2 * a.ld + (e - n1), 0.0);
   }
+}
+
+template <class O>
+__global__ void k_permute4_pad(PermArgs a, O out) {
+  perm_pad(a, out, vtid());
+}
+
+// Up to kMaxPermJobs independent permutes (distinct destinations, no source
+// another job writes) in one launch: the blocks of each job's main pass (one
+// per destination row, or one per slice), then the padding blocks of the
+// slice-form jobs; each block finds its job by the block prefix sums.
+template <class O>
+struct PermBatch {
+  PermArgs a[kMaxPermJobs];
+  SliceStrides t[kMaxPermJobs];
+  O out[kMaxPermJobs];
+  int slice[kMaxPermJobs];
+  int start[kMaxPermJobs + 1];   // main blocks of job j: [start[j], start[j+1])
+  int pstart[kMaxPermJobs + 1];  // padding blocks, numbered after all main blocks
+  int count;
+};
+
+static_assert(sizeof(PermBatch<VOutBF16x3>) <= 4096 - 64, "kernel arguments must fit in 4 KiB");
+
+template <class O>
+__global__ void __launch_bounds__(256)
+k_permute4_batch(PermBatch<O> b) {
+  extern __shared__ double ps_smem[];
+  const int bid = blockIdx.x;
+  const int nmain = b.start[b.count];
+  if (bid < nmain) {
+    int j = 0;
+    while (j + 1 < b.count && bid >= b.start[j + 1]) ++j;
+    const int local = bid - b.start[j];
+    if (b.slice[j]) perm_slice(b.a[j], b.t[j], b.out[j], local, ps_smem);
+    else perm_row(b.a[j], b.out[j], local);
+    return;
+  }
+  const int pb = bid - nmain;
+  int j = 0;
+  while (j + 1 < b.count && pb >= b.pstart[j + 1]) ++j;
+  perm_pad(b.a[j], b.out[j], (int64_t)(pb - b.pstart[j]) * 256 + threadIdx.x);
 }
 
 // out[x,y] (+)= sum_t c_t sum_{u,v} T_t[x sx + y sy + u su + v sv] M_t[u r + v]
@@ -416,17 +467,45 @@ __global__ void k_identity(int r, double *__restrict__ I) {
 }
 
 // ---------------------------------------------------------------------------
+// Form of a permute: q >= 0 the slice form moving position q (stage flags per
+// source), q < 0 the row form.
+static void permute_form(const PermArgs &a, int &q, int &stage1, int &stage2) {
+  auto unit = [](const int64_t st[4]) {
+    for (int p = 0; p < 3; ++p)
+      if (st[p] == 1) return p;
+    return -1;
+  };
+  q = -1;
+  stage1 = stage2 = 0;
+  const bool d1 = a.s1[3] == 1, d2 = !a.src2 || a.s2[3] == 1;
+  if (!d1) {
+    q = unit(a.s1);
+    stage1 = 1;
+    if (q >= 0 && !d2) {
+      if (a.s2[q] == 1) stage2 = 1;
+      else q = -1;
+    }
+  } else if (!d2) {
+    q = unit(a.s2);
+    stage2 = 1;
+  }
+}
+
+static SliceStrides slice_strides(const PermArgs &a, int q, int stage1, int stage2) {
+  // destination offset per unit of each index position (row = (0,1), col = (2,3))
+  const int64_t os[4] = {(int64_t)a.r * a.ld, a.ld, a.r, 1};
+  const int f1 = q == 0 ? 1 : 0, f2 = q == 2 ? 1 : 2;
+  return SliceStrides{a.s1[f1], a.s1[f2], a.s1[q], a.s2[f1], a.s2[f2], a.s2[q],
+                      os[q],    os[f1],   os[f2], stage1,   stage2};
+}
+
 template <class O>
 static hipError_t launch_permute4_o(const PermArgs &a, int q, int stage1, int stage2, O out, hipStream_t s) {
   if (q < 0) {
     hipLaunchKernelGGL((k_permute4<O>), dim3((unsigned)a.rows), dim3(256), 0, s, a, out);
     return hipGetLastError();
   }
-  // destination offset per unit of each index position (row = (0,1), col = (2,3))
-  const int64_t os[4] = {(int64_t)a.r * a.ld, a.ld, a.r, 1};
-  const int f1 = q == 0 ? 1 : 0, f2 = q == 2 ? 1 : 2;
-  const SliceStrides t{a.s1[f1], a.s1[f2], a.s1[q], a.s2[f1], a.s2[f2], a.s2[q],
-                       os[q],    os[f1],   os[f2], stage1,   stage2};
+  const SliceStrides t = slice_strides(a, q, stage1, stage2);
   const size_t lds = (size_t)a.r * (a.r + 1) * sizeof(double);
   hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(&k_permute4_slice<O>),
                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
@@ -444,24 +523,8 @@ hipError_t launch_permute4(GemmPrec prec, const PermArgs &a, const OperandRef &o
   // position 3 but another position q < 3; a source whose unit stride is
   // position 3 is read directly.  Otherwise (all sources contiguous along
   // position 3, or two sources needing different slices) the row form.
-  auto unit = [](const int64_t st[4]) {
-    for (int p = 0; p < 3; ++p)
-      if (st[p] == 1) return p;
-    return -1;
-  };
-  int q = -1, stage1 = 0, stage2 = 0;
-  const bool d1 = a.s1[3] == 1, d2 = !a.src2 || a.s2[3] == 1;
-  if (!d1) {
-    q = unit(a.s1);
-    stage1 = 1;
-    if (q >= 0 && !d2) {
-      if (a.s2[q] == 1) stage2 = 1;
-      else q = -1;
-    }
-  } else if (!d2) {
-    q = unit(a.s2);
-    stage2 = 1;
-  }
+  int q, stage1, stage2;
+  permute_form(a, q, stage1, stage2);
   if (a.accumulate) {
     if (prec != GEMM_F64) return hipErrorInvalidValue;
     return launch_permute4_o(a, q, stage1, stage2, VOutF64Acc{static_cast<double *>(out.hi)}, s);
@@ -660,6 +723,83 @@ hipError_t launch_proj(ProjKind k, int r, double c, const double *x, double *out
 hipError_t launch_identity(int r, double *I, hipStream_t s) {
   hipLaunchKernelGGL(k_identity, vgrid((int64_t)r * r), dim3(256), 0, s, r, I);
   return hipGetLastError();
+}
+
+}  // namespace acse
+
+namespace acse {
+
+template <class O>
+static hipError_t launch_batch_o(const PermArgs *a, const O *out, int count, hipStream_t s) {
+  PermBatch<O> b{};
+  b.count = count;
+  int nmain = 0, npadb = 0, r = 0;
+  bool any_slice = false;
+  for (int j = 0; j < count; ++j) {
+    int q, st1, st2;
+    permute_form(a[j], q, st1, st2);
+    b.a[j] = a[j];
+    b.out[j] = out[j];
+    b.slice[j] = q >= 0;
+    if (q >= 0) b.t[j] = slice_strides(a[j], q, st1, st2);
+    b.start[j] = nmain;
+    nmain += q >= 0 ? a[j].r * a[j].r : (int)a[j].rows;
+    r = std::max(r, a[j].r);
+    any_slice = any_slice || q >= 0;
+  }
+  b.start[count] = nmain;
+  for (int j = 0; j < count; ++j) {
+    b.pstart[j] = npadb;
+    if (b.slice[j] && !a[j].accumulate) {
+      const int64_t r2 = (int64_t)a[j].r * a[j].r;
+      const int64_t npad = r2 * (a[j].ld - r2) + (a[j].rows - r2) * a[j].ld;
+      npadb += (int)((npad + 255) / 256);
+    }
+  }
+  b.pstart[count] = npadb;
+  const size_t lds = any_slice ? (size_t)r * (r + 1) * sizeof(double) : 0;
+  if (lds) {
+    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(&k_permute4_batch<O>),
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
+  }
+  hipLaunchKernelGGL((k_permute4_batch<O>), dim3((unsigned)(nmain + npadb)), dim3(256), lds, s, b);
+  return hipGetLastError();
+}
+
+hipError_t launch_permute4_batch(const GemmPrec *prec, const PermArgs *a, const OperandRef *out, int count,
+                                 hipStream_t s) {
+  // consecutive jobs of one destination type go out together
+  for (int j0 = 0; j0 < count;) {
+    const bool acc = a[j0].accumulate != 0;
+    const GemmPrec p = prec[j0];
+    if (acc && p != GEMM_F64) return hipErrorInvalidValue;
+    int j1 = j0 + 1;
+    while (j1 < count && j1 - j0 < kMaxPermJobs && prec[j1] == p && (a[j1].accumulate != 0) == acc) ++j1;
+    const int n = j1 - j0;
+    hipError_t e = hipSuccess;
+    if (acc) {
+      VOutF64Acc o[kMaxPermJobs];
+      for (int j = 0; j < n; ++j) o[j] = VOutF64Acc{static_cast<double *>(out[j0 + j].hi)};
+      e = launch_batch_o(a + j0, o, n, s);
+    } else if (p == GEMM_F64) {
+      VOutF64 o[kMaxPermJobs];
+      for (int j = 0; j < n; ++j) o[j] = VOutF64{static_cast<double *>(out[j0 + j].hi)};
+      e = launch_batch_o(a + j0, o, n, s);
+    } else if (p == GEMM_F32) {
+      VOutF32 o[kMaxPermJobs];
+      for (int j = 0; j < n; ++j) o[j] = VOutF32{static_cast<float *>(out[j0 + j].hi)};
+      e = launch_batch_o(a + j0, o, n, s);
+    } else {
+      VOutBF16x3 o[kMaxPermJobs];
+      for (int j = 0; j < n; ++j)
+        o[j] = VOutBF16x3{static_cast<__bf16 *>(out[j0 + j].hi), static_cast<__bf16 *>(out[j0 + j].lo)};
+      e = launch_batch_o(a + j0, o, n, s);
+    }
+    if (e != hipSuccess) return e;
+    j0 = j1;
+  }
+  return hipSuccess;
 }
 
 }  // namespace acse
