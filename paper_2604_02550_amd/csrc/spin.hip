@@ -202,90 +202,91 @@ __global__ void __launch_bounds__(256) k_so_trace_y(int n, const double *__restr
   Y[e] = acc;
 }
 
-// One thread per output element (i,j,k,l), the sum over a in a fixed order.
-// Y and cs conserve spin (Y_ka is zero unless a has the spin of k), so only
-// the spin-conserving outputs receive a contribution, and a runs over the
-// spin orbitals of k's spin.
+// One thread per (i, j, four consecutive k of one spin, l): the sum over a in
+// a fixed order, each cs element read once for the four k.  Y and cs conserve
+// spin (Y_ka is zero unless a has the spin of k), so only the spin-conserving
+// outputs receive a contribution, and a runs over the spin orbitals of k's spin.
 __global__ void __launch_bounds__(256)
 k_so_tpl(int n, double c, const double *__restrict__ Y, const double *__restrict__ cs, double *__restrict__ B) {
+  const int r = n / 2, kq = (r + 3) / 4;  // k groups per spin
   const int64_t n2 = (int64_t)n * n;
   const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  if (e >= n2 * n2) return;
-  const int r = n / 2;
-  const int l = (int)(e % n), k = (int)((e / n) % n), j = (int)((e / n2) % n), i = (int)(e / (n2 * n));
-  if ((i >= r) + (j >= r) != (k >= r) + (l >= r)) return;
-  const int64_t ij = e / n2;
-  const int a0 = k >= r ? r : 0;
-  const double *y = Y + (int64_t)k * n, *q = cs + ij * n2 + l;
-  double acc = 0.0;
-  for (int a = a0; a < a0 + r; ++a) acc += y[a] * q[(int64_t)a * n];
-  B[e] += c * acc;
+  if (e >= n2 * 2 * kq * n) return;
+  const int l = (int)(e % n);
+  const int64_t rest = e / n;
+  const int g = (int)(rest % (2 * kq));
+  const int64_t ij = rest / (2 * kq);
+  const int i = (int)(ij / n), j = (int)(ij % n);
+  const int sk = g / kq, k0 = sk * r + (g % kq) * 4;
+  const int kend = min(k0 + 4, sk * r + r);
+  if ((i >= r) + (j >= r) != sk + (l >= r)) return;
+  const double *q = cs + ij * n2 + l;
+  double acc[4] = {0.0, 0.0, 0.0, 0.0};
+  for (int a = sk * r; a < sk * r + r; ++a) {
+    const double v = q[(int64_t)a * n];
+#pragma unroll
+    for (int t = 0; t < 4; ++t)
+      if (k0 + t < kend) acc[t] += Y[(int64_t)(k0 + t) * n + a] * v;
+  }
+  for (int t = 0; t < 4; ++t)
+    if (k0 + t < kend) B[ij * n2 + (int64_t)(k0 + t) * n + l] += c * acc[t];
 }
 
-// One workgroup per (letter values of the two positions other than u and 3,
-// 32 x 32 tile over positions u and 3), u the operand position the source
-// reads with unit stride: the tile is read along u and written along position
-// 3 through LDS.  If the source's unit stride is position 3 itself (u = 3),
-// the tile is read and written along position 3 directly.
+// One workgroup per (letter values of the two positions other than u and 3),
+// looping over the 32 x 32 tiles of positions u and 3, u the operand position
+// the source reads with unit stride: a tile is read along u and written along
+// position 3 through LDS.  If the source's unit stride is position 3 itself
+// (u = 3), tiles are read and written along position 3 directly.  Addresses
+// are sums of per-position terms: letter value L of operand position t adds
+// L b[t] + (L >= r) (o[t] - r b[t]) to the destination offset and L st[t] to
+// the source offset; the source element conserves spin iff
+// sum_t c[t] (L_t >= r) = 0.
 struct SoPackArgs {
-  int64_t st[4];
-  int u, v, w;  // u: the unit-stride position (3: none other); v, w: the fixed ones
-  int src_pos[4];  // source position of each operand position
-  int pair;        // the source's conservation pair (with position 0)
+  int64_t st[4];   // source strides of the operand positions
+  int64_t b[4];    // destination offset per unit of the spatial index of each position
+  int64_t o[4];    // destination offset of a beta letter at each position
+  int c[4];        // +1 / -1: the side of the source's conservation pair each position is on
+  int u, v, w;     // u: the unit-stride position (3: none other); v, w: the fixed ones
 };
-// Whether the source element behind operand letter values L conserves spin.
-__device__ inline bool so_pack_keep(const SoPackArgs &a, int r, const int L[4]) {
-  int sp[4];
-  for (int t = 0; t < 4; ++t) sp[a.src_pos[t]] = L[t] >= r;
-  int o0 = 0, o1 = 0, k = 0;
-  for (int t = 1; t < 4; ++t)
-    if (t != a.pair) { if (k++ == 0) o0 = t; else o1 = t; }
-  return sp[0] + sp[a.pair] == sp[o0] + sp[o1];
-}
 __global__ void __launch_bounds__(256)
-k_so_pack(int r, int64_t rpad, int64_t kc, const double *__restrict__ src, SoPackArgs a, double *__restrict__ out) {
+k_so_pack(int r, const double *__restrict__ src, SoPackArgs a, double *__restrict__ out) {
   __shared__ double tile[32][33];
   const int n = 2 * r;
   const int nt = (n + 31) / 32;
-  const int64_t ld = 4 * kc;
-  int bid = blockIdx.x;
-  const int tu = bid % nt; bid /= nt;
-  const int t3 = bid % nt; bid /= nt;
-  const int Lw = bid % n, Lv = bid / n;
-  auto oaddr = [&](const int L[4]) {
-    const int s0 = L[0] >= r, s1 = L[1] >= r, s2 = L[2] >= r, s3 = L[3] >= r;
-    return ((int64_t)(2 * s0 + s1) * rpad + (int64_t)(L[0] - s0 * r) * r + (L[1] - s1 * r)) * ld +
-           (int64_t)(2 * s2 + s3) * kc + (int64_t)(L[2] - s2 * r) * r + (L[3] - s3 * r);
-  };
-  auto saddr = [&](const int L[4]) {
-    return L[0] * a.st[0] + L[1] * a.st[1] + L[2] * a.st[2] + L[3] * a.st[3];
-  };
+  const int Lw = blockIdx.x % n, Lv = blockIdx.x / n;
+  auto off = [&](int t, int L) { return L * a.b[t] + (L >= r ? a.o[t] - r * a.b[t] : 0); };
+  const int64_t obase = off(a.v, Lv) + off(a.w, Lw);
+  const int64_t sbase = Lv * a.st[a.v] + Lw * a.st[a.w];
+  const int cbase = a.c[a.v] * (Lv >= r) + a.c[a.w] * (Lw >= r);
   if (a.u == 3) {
-    // positions v, w fixed by the block, tu indexes the third free position
-    // (stored in a.w's slot order: v, w, then the remaining one), t3 position 3
-    for (int q = threadIdx.x; q < 32 * 32; q += 256) {
-      const int i3 = q % 32, iu = q / 32;
-      int L[4];
-      L[a.v] = Lv; L[a.w] = Lw;
-      const int third = 3 - a.v - a.w;  // the position among 0..2 not v, w
-      L[third] = tu * 32 + iu;
-      L[3] = t3 * 32 + i3;
-      if (L[third] < n && L[3] < n && so_pack_keep(a, r, L)) out[oaddr(L)] = src[saddr(L)];
+    // the third free position (the one of 0..2 other than v, w) and position 3
+    const int third = 3 - a.v - a.w;
+    for (int tt = 0; tt < nt * nt; ++tt) {
+      const int tu = tt / nt, t3 = tt % nt;
+      for (int q = threadIdx.x; q < 32 * 32; q += 256) {
+        const int Lt = tu * 32 + q / 32, L3 = t3 * 32 + q % 32;
+        if (Lt >= n || L3 >= n) continue;
+        if (cbase + a.c[third] * (Lt >= r) + a.c[3] * (L3 >= r) != 0) continue;
+        out[obase + off(third, Lt) + off(3, L3)] = src[sbase + Lt * a.st[third] + L3];
+      }
     }
     return;
   }
-  for (int q = threadIdx.x; q < 32 * 32; q += 256) {
-    const int iu = q % 32, i3 = q / 32;
-    int L[4];
-    L[a.v] = Lv; L[a.w] = Lw; L[a.u] = tu * 32 + iu; L[3] = t3 * 32 + i3;
-    tile[i3][iu] = (L[a.u] < n && L[3] < n && so_pack_keep(a, r, L)) ? src[saddr(L)] : 0.0;
-  }
-  __syncthreads();
-  for (int q = threadIdx.x; q < 32 * 32; q += 256) {
-    const int i3 = q % 32, iu = q / 32;
-    int L[4];
-    L[a.v] = Lv; L[a.w] = Lw; L[a.u] = tu * 32 + iu; L[3] = t3 * 32 + i3;
-    if (L[a.u] < n && L[3] < n && so_pack_keep(a, r, L)) out[oaddr(L)] = tile[i3][iu];
+  for (int tt = 0; tt < nt * nt; ++tt) {
+    const int tu = tt / nt, t3 = tt % nt;
+    __syncthreads();  // the previous tile's reads of LDS are done
+    for (int q = threadIdx.x; q < 32 * 32; q += 256) {
+      const int Lu = tu * 32 + q % 32, L3 = t3 * 32 + q / 32;
+      const bool ok = Lu < n && L3 < n && cbase + a.c[a.u] * (Lu >= r) + a.c[3] * (L3 >= r) == 0;
+      tile[q / 32][q % 32] = ok ? src[sbase + Lu + L3 * a.st[3]] : 0.0;
+    }
+    __syncthreads();
+    for (int q = threadIdx.x; q < 32 * 32; q += 256) {
+      const int Lu = tu * 32 + q / 32, L3 = t3 * 32 + q % 32;
+      if (Lu >= n || L3 >= n) continue;
+      if (cbase + a.c[a.u] * (Lu >= r) + a.c[3] * (L3 >= r) != 0) continue;
+      out[obase + off(a.u, Lu) + off(3, L3)] = tile[q % 32][q / 32];
+    }
   }
 }
 
@@ -529,27 +530,32 @@ hipError_t launch_so_trace_y(int n, const double *W, double *Y, hipStream_t s) {
 }
 
 hipError_t launch_so_tpl(int n, double c, const double *Y, const double *cs, double *B, hipStream_t s) {
-  hipLaunchKernelGGL(k_so_tpl, grid1((int64_t)n * n * n * n), dim3(256), 0, s, n, c, Y, cs, B);
+  const int r = n / 2, kq = (r + 3) / 4;
+  hipLaunchKernelGGL(k_so_tpl, grid1((int64_t)n * n * 2 * kq * n), dim3(256), 0, s, n, c, Y, cs, B);
   return hipGetLastError();
 }
 
 hipError_t launch_so_pack(int r, int64_t rpad, int64_t kc, const double *src, const int64_t st[4],
                           const int src_pos[4], int pair, double *out, hipStream_t s) {
   SoPackArgs a{};
+  const int64_t ld = 4 * kc;
+  // destination: row (2 s0 + s1) rpad + l0 r + l1, column (2 s2 + s3) kc + l2 r + l3
+  const int64_t bb[4] = {(int64_t)r * ld, ld, r, 1};
+  const int64_t oo[4] = {2 * rpad * ld, rpad * ld, 2 * kc, kc};
   for (int t = 0; t < 4; ++t) {
     a.st[t] = st[t];
-    a.src_pos[t] = src_pos[t];
+    a.b[t] = bb[t];
+    a.o[t] = oo[t];
+    a.c[t] = (src_pos[t] == 0 || src_pos[t] == pair) ? 1 : -1;
   }
-  a.pair = pair;
   a.u = 3;
   for (int t = 0; t < 3; ++t)
     if (st[t] == 1) a.u = t;
   // the fixed positions: the two of 0..2 other than u (for u = 3: positions 0 and 1)
   if (a.u == 3) { a.v = 0; a.w = 1; }
   else { a.v = a.u == 0 ? 1 : 0; a.w = a.u == 2 ? 1 : 2; }
-  const int n = 2 * r, nt = (n + 31) / 32;
-  hipLaunchKernelGGL(k_so_pack, dim3((unsigned)((int64_t)n * n * nt * nt)), dim3(256), 0, s, r, rpad, kc, src, a,
-                     out);
+  const int n = 2 * r;
+  hipLaunchKernelGGL(k_so_pack, dim3((unsigned)((int64_t)n * n)), dim3(256), 0, s, r, src, a, out);
   return hipGetLastError();
 }
 
