@@ -67,6 +67,19 @@ def test_option_arrays_must_cover_r(ctx):
     acse._check_opts(acse.Context.options(active=[1, 0, 1, 0, 0], sigma=[1, 1, -1, -1, -1]), 5)
 
 
+def test_spin_calls_take_occupations_per_spin_orbital(ctx):
+    """The _spin calls take 2r NY occupations (alpha orbitals first), the
+    singlet calls r; the binding refuses the other length before the library."""
+    prob = acse.ProblemSpin(4, 3, 1, 0, 0, 0, 0, 0, 0, 0)
+    with pytest.raises(ValueError, match="2r = 8 spin orbitals"):
+        ctx.step_spin_raw(prob, 1e-3, acse.Context.options(sigma=[1, 1, -1, -1]))
+    with pytest.raises(ValueError, match="2r = 8 spin orbitals"):
+        ctx.solve_spin_raw(prob, acse.Context.options(sigma=[1] * 4), acse.SolveOptions())
+    acse._check_opts(acse.Context.options(sigma=[1, 1, 1, -1, 1, -1, -1, -1]), 4, spin=True)
+    with pytest.raises(ValueError, match="r = 4 orbitals"):
+        acse._check_opts(acse.Context.options(sigma=[1, 1, 1, -1, 1, -1, -1, -1]), 4)
+
+
 def test_outputs_checked_before_the_library(ctx):
     prob = acse.Problem(4, 2, 2, 0, 0, 0, 0, 0)
     opts = acse.Context.options()
