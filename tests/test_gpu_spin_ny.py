@@ -117,6 +117,23 @@ def test_spin_ny_residual_and_step(ctx, name):
         assert diff > 1e-6 * scale
 
 
+@pytest.mark.parametrize("r,Na,Nb", [(2, 1, 1), (4, 3, 0), (5, 2, 0), (5, 4, 1), (3, 1, 1)])
+def test_spin_ny_edge_counts(ctx, r, Na, Nb):
+    """The smallest size (2r = 4 spin orbitals, one GEMM tile with a ragged
+    edge), an empty beta shell (beta blocks zero, every beta occupation -1), a
+    single beta electron and the smallest open- and closed-shell counts."""
+    p = gen.spin_problem(r, Na, Nb, 2 * r, seed=70 + r + Na)
+    sig = ost.sigma_open_shell(r, Na, Nb)
+    print(f"[spin ny edge] r={r} Na={Na} Nb={Nb}", flush=True)
+    o = ost.step_spin(*_oracle_args(p), 1e-3, sigma_so=sig)
+    g = ctx.step_spin(*_args(p), eps=1e-3, return_ru=True, sigma=True)
+    for keys in (("R_aa", "R_bb", "R_ab"), ("U_aa", "U_bb", "U_ab"), ("d2aa", "d2bb", "d2ab")):
+        scale = max(np.abs(o[k]).max() for k in keys)
+        for k in keys:
+            assert np.abs(cpu(g[k]) - o[k]).max() <= TOL * max(scale, 1e-300), k
+    assert abs(g["energy"] - o["energy"]) <= TOL * max(1.0, abs(o["energy"]))
+
+
 def test_spin_ny_r16_residual(ctx):
     """The largest size of this file: 2r = 32 spin orbitals, 1024-row GEMMs."""
     p = gen.spin_problem(16, 9, 6, 32, seed=4)
