@@ -276,6 +276,21 @@ def test_residual_vjp_ny_fp64_vs_oracle(ctx, name, kind):
     assert max(rel(val[k], ref[k]) for k in KEYS) > 1e-6
 
 
+@pytest.mark.parametrize("r,N", [(2, 2), (3, 2), (3, 4)])
+def test_residual_vjp_ny_smallest_sizes(ctx, r, N):
+    """The NY adjoint at the smallest sizes (2r = 4 and 6 spin orbitals: one
+    ragged tile in every spin-block product)."""
+    p = gen.problem(r, N, 2 * r, seed=9)
+    sig = [1 if q < N // 2 else -1 for q in range(r)]
+    print(f"[residual_vjp_ny] r={r} N={N}", flush=True)
+    Rb = gen.cotangent(np.random.default_rng(3), r)
+    ref = adj.residual_vjp(p["h"], p["V"], p["N"], p["gamma"], p["d2aa"], p["d2ab"], *Rb, sigma=sig)
+    got = gpu_vjp(ctx, p, Rb, sigma=True)
+    for k in KEYS:
+        assert rel(got[k], ref[k]) < TOL64, (k, rel(got[k], ref[k]))
+        assert maxrel(got[k], ref[k]) < TOL64, (k, maxrel(got[k], ref[k]))
+
+
 def test_residual_vjp_ny_int8crt_vs_oracle(ctx):
     p = PROBLEMS["r10"]()
     sig = ny_sigma(p, "scattered")
