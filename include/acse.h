@@ -159,10 +159,13 @@ typedef struct {
  *                  adjoint (acse_residual_vjp) and the quadratic step control
  *                  of acse_solve (which needs it) take the NY share's adjoint
  *                  for r <= 64 (ACSE_ERR_UNSUPPORTED above): FP64 over
- *                  spin-orbital tensors (n = 2r; 15 n^2 x n^2 x n^2 GEMMs), its
- *                  first call allocating (12 n^4 + 2 n^2 + n) doubles and two
- *                  n^2-row operand buffers for its r (2.2 GB at r = 32),
- *                  reallocated when a larger r comes, kept until acse_destroy. */
+ *                  spin-orbital tensors (n = 2r) as 15 pairwise contractions,
+ *                  each run as the 10 of its 64 r^2 x r^2 x r^2 spin-block
+ *                  products whose operand blocks conserve spin; its first call
+ *                  allocating 12 n^4 doubles and two operand buffers of
+ *                  16 round_up(r^2, 256) round_up(r^2, 64) doubles for its r
+ *                  (1.9 GB at r = 32, 11.3 GB at r = 50), reallocated when a
+ *                  larger r comes, kept until acse_destroy. */
 typedef enum { ACSE_RECON_V = 0, ACSE_RECON_NY = 1 } acse_reconstruction;
 
 /* acse_options.flags: run the general-size kernels at every r (the one-index
@@ -466,11 +469,12 @@ acse_status acse_residual_noalloc(void *hip_stream, const acse_problem *prob, co
  * either reconstruction.  With ACSE_RECON_NY (r <= 64, otherwise
  * ACSE_ERR_UNSUPPORTED) the NY 3-cumulant of Eq. (8) joins both maps of a
  * step: its share runs in FP64 over spin-orbital tensors (n = 2r spin
- * orbitals; six n^2 x n^2 x n^2 GEMMs per map, each eight times the flops of
- * a spatial-block product), also under ACSE_INT8CRT; its first call
- * allocates (6 n^4 + n^2 + n) doubles and two n^2-row operand buffers for its
- * r (1.1 GB at r = 32), reallocated when a larger r comes and kept until
- * acse_destroy.  The first call allocates a workspace for
+ * orbitals; six pairwise contractions per map, each run as the 10 of its 64
+ * r^2 x r^2 x r^2 spin-block products whose operand blocks conserve spin),
+ * also under ACSE_INT8CRT; its first call allocates 6 n^4 doubles and two
+ * operand buffers of 16 round_up(r^2, 256) round_up(r^2, 64) doubles for its
+ * r (1.1 GB at r = 32, 6.5 GB at r = 50), reallocated when a larger r comes
+ * and kept until acse_destroy.  The first call allocates a workspace for
  * r_max: 48 r_max^4 doubles and 25 GEMM operand buffers (about 3.7 GB at
  * r_max = 50), kept until acse_destroy; the first ACSE_INT8CRT call adds the
  * residues of those buffers and of one launch's products (about 3.0 GB at
