@@ -2793,8 +2793,22 @@ acse_status run_lanes(acse_ctx c, int count, const acse_problem *probs, GemmPrec
     return map_back(c, p, -1.0, Raa ? Raa[i] : w.Raa, Rab ? Rab[i] : w.Rab, none, nullptr, nullptr,
                     plan.norms + i, w);
   };
-  for (int i : order)
-    if ((st = one(i)) != ACSE_OK) break;
+  // each lane's instances in decreasing size; with the int8, FP32 and split-BF16
+  // products every second lane takes its own in increasing size, so that the
+  // lanes' memory-bound fronts and compute-bound products fall at different
+  // times (the FP64 products, which dominate each instance more, keep the
+  // decreasing order there); issued round-robin over the lanes so that every
+  // lane starts at once
+  std::vector<std::vector<int>> per(ns);
+  for (int i : order) per[lane[i]].push_back(i);
+  if (prec != GEMM_F64)
+    for (int q = 1; q < ns; q += 2) std::reverse(per[q].begin(), per[q].end());
+  size_t depth = 0;
+  for (int q = 0; q < ns; ++q) depth = std::max(depth, per[q].size());
+  st = ACSE_OK;
+  for (size_t t = 0; t < depth && st == ACSE_OK; ++t)
+    for (int q = 0; q < ns && st == ACSE_OK; ++q)
+      if (t < per[q].size()) st = one(per[q][t]);
   // a failing launch still rejoins the side streams before returning
   const acse_status sj = join_sides(c, ns);
   return st != ACSE_OK ? st : sj;
