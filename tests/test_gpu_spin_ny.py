@@ -4,13 +4,20 @@ occupations) against the FP64 oracle's spin-block maps.
 
 Same bar as the Valdemoro spin-block tests: max-elementwise and normwise
 relative error <= 1e-10 per block (relative to the largest block), scalars
-relative 1e-10.  Sizes r = 3 ... 16 (2r = 6 ... 32 spin orbitals; the NY share
-runs its GEMMs over (2r)^2 rows, so 36 ... 1024 against 64/128 tiles with
-ragged tails); doublets, triplets, an S_z = 1 determinant (2-cumulant zero:
-the NY share vanishes and the residual is the Valdemoro one), explicit
-occupations other than the default, the int8 products of the Valdemoro part
-and the Euler iteration.
+relative 1e-10.  Sizes r = 2 ... 16 (2r = 4 ... 32 spin orbitals; the NY share
+runs r^2 x r^2 x r^2 spin-block products, 4 ... 256 rows against 64/128 tiles
+with ragged tails); doublets, triplets, an S_z = 1 determinant (2-cumulant
+zero: the NY share vanishes and the residual is the Valdemoro one), empty and
+single-electron beta shells, explicit occupations other than the default, the
+int8 products of the Valdemoro part and the Euler iteration.  At the full size
+(r = 50, N_alpha = 16, N_beta = 14, the open-shell workload the bench times)
+the residual in FP64 and int8 against stored oracle values
+(tests/golden/r50_spin_ny_residual.json, written by
+tests/golden/make_golden_spin_ny.py, which calls only the oracle).
 """
+import json
+import os
+
 import numpy as np
 import pytest
 
@@ -218,3 +225,29 @@ def test_spin_ny_solve_matches_oracle_iteration(ctx):
     scale = max(np.abs(o[k]).max() for k in ("d2aa", "d2bb", "d2ab"))
     for k in ("d2aa", "d2bb", "d2ab"):
         assert np.abs(cpu(g[k]) - o[k]).max() <= TOL * scale, k
+
+
+SPIN_NY_GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "r50_spin_ny_residual.json")
+
+
+@pytest.mark.parametrize("precision", ["fp64", "int8crt"])
+def test_r50_spin_ny_residual_vs_stored_oracle(acse, precision):
+    """Full size, the open-shell NY leg of the bench (default open-shell
+    occupations): 96 sampled elements of each residual block, the block norms
+    and ||R||^2 against the stored oracle values at 1e-10."""
+    g = json.load(open(SPIN_NY_GOLDEN))
+    p = gen.named_spin(g["workload"])
+    print(f"[spin ny] r50 stored oracle {precision}", flush=True)
+    ctx = acse.Context(r_max=p["r"])
+    try:
+        Raa, Rbb, Rab, n2 = ctx.residual_spin(*_args(p), sigma=True, precision=precision)
+        got = dict(R_aa=cpu(Raa), R_bb=cpu(Rbb), R_ab=cpu(Rab))
+        idx = [tuple(t) for t in g["index"]]
+        scale = max(max(abs(x) for x in g["samples"][k]) for k in got)
+        for k, v in got.items():
+            val = np.array([v[t] for t in idx])
+            assert np.abs(val - np.array(g["samples"][k])).max() <= TOL * scale, k
+            assert abs(float(np.linalg.norm(v)) - g["norms"][k]) <= TOL * g["norms"][k], k
+        assert abs(n2 - g["norm2"]) <= TOL * g["norm2"]
+    finally:
+        ctx.close()

@@ -318,3 +318,37 @@ def test_autograd_function_ny(acse, ctx):
                            sigma=sig)
     for t, k in zip(x, KEYS):
         assert rel(cpu(t.grad), ref[k]) < TOL64, k
+
+
+def test_residual_vjp_ny_r50_finite_difference(acse):
+    """The NY adjoint at the size the bench times (r = 50, N = 30, default
+    occupations): <gradient, direction> against central finite differences
+    of <Rbar, R> along one structured direction per input, R from the NY
+    residual on the GPU (itself checked against stored oracle values at this
+    size in test_gpu_ny.py)."""
+    import torch
+    p = gen.named("r50")
+    rng = np.random.default_rng(50)
+    Rb = gen.cotangent(rng, p["r"])
+    dirs = gen.symmetric_direction(rng, p["r"])
+    ctx = acse.Context(r_max=p["r"])
+    try:
+        dev = ctx.device
+        Rbt = [torch.as_tensor(a, device=dev) for a in Rb]
+
+        def loss(**over):
+            q = {k: over.get(k, p[k]) for k in KEYS}
+            Raa, Rab, _ = ctx.residual(q["h"], q["V"], q["gamma"], q["d2aa"], q["d2ab"], p["N"] // 2, sigma=True)
+            return float((Rbt[0] * Raa).sum() + (Rbt[1] * Rab).sum())
+
+        print("[vjp50 ny] adjoint", flush=True)
+        got = gpu_vjp(ctx, p, Rb, sigma=True)
+        t = 1e-5
+        for k in KEYS:
+            fd = (loss(**{k: p[k] + t * dirs[k]}) - loss(**{k: p[k] - t * dirs[k]})) / (2 * t)
+            an = float(np.sum(got[k] * dirs[k]))
+            scale = max(abs(fd), np.linalg.norm(got[k]))
+            print(f"[vjp50 ny] {k} fd {fd:.10e} an {an:.10e}", flush=True)
+            assert abs(an - fd) <= 1e-7 * scale, (k, an, fd)
+    finally:
+        ctx.close()
