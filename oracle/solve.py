@@ -72,6 +72,30 @@ def norm_slope(h, V, N, gamma, d2aa, d2ab, Raa, Rab, uaa, uab, sigma=None):
     return float(np.sum(g["d2aa"] * uaa) + np.sum(g["d2ab"] * uab) + np.sum(g["gamma"] * dgamma))
 
 
+def norm_slope_spin(h, V, Na, Nb, ga, gb, d2aa, d2bb, d2ab, uaa, ubb, uab, sigma_so=None):
+    """f'(0) for f(s) = ||R(2D + s U, 1D + s dD)||^2 over spin orbitals of a
+    state of any S_z, dD the 1-RDMs contracted from U (the contraction is
+    linear): reverse-mode differentiation (torch.autograd) of the torch
+    residual map with respect to s, along the straight line in the RDMs."""
+    import torch
+    r = h.shape[0]
+    N = Na + Nb
+    K = torch.from_numpy(rdm.reduced_hamiltonian(np.asarray(h, float), np.asarray(V, float), N))
+    d1, d2 = rdm.spin_blocks_to_spin_orbital(ga, gb, d2aa, d2bb, d2ab)
+    z = np.zeros((r, r))
+    _, u2 = rdm.spin_blocks_to_spin_orbital(z, z, uaa, ubb, uab)
+    u1 = rdm.contract_to_1rdm(u2, N)
+    a, b = rdm.spin_blocks(r)
+    u1[a, b] = 0.0   # the 1-RDM blocks are spin-diagonal
+    u1[b, a] = 0.0
+    sv = torch.zeros((), dtype=torch.float64, requires_grad=True)
+    D1 = torch.from_numpy(d1) + sv * torch.from_numpy(u1)
+    D2 = torch.from_numpy(d2) + sv * torch.from_numpy(u2)
+    R = residual_map(K, D1, D2, hermitian=True, sigma_so=sigma_so)
+    (g,) = torch.autograd.grad((R * R).sum(), sv)
+    return float(g)
+
+
 def quadratic_trial_step(f0, g0, eps, f_eps, eps_max):
     """Second step size of QUADRATIC, or None: the minimiser of the parabola
     through f(0) = f0 with slope g0 and f(eps) = f_eps, clamped to
@@ -174,17 +198,19 @@ def euler(h, V, N, gamma, d2aa, d2ab, eps=1e-3, de_tol=1e-6, max_iter=100, contr
 
 
 def euler_spin(h, V, Na, Nb, ga, gb, d2aa, d2bb, d2ab, eps=1e-3, de_tol=1e-6, max_iter=100, control=FIXED,
-               max_halvings=8, active=None, sigma_so=None):
+               max_halvings=8, active=None, sigma_so=None, eps_max=0.0):
     """The iteration of ``euler`` for a state of any S_z, on its three 2-RDM
     spin blocks (alpha-alpha, beta-beta, alpha-beta) and one 1-RDM per spin:
-    the same stopping rules and the FIXED and BACKTRACK controls; each block is
-    rescaled to its own trace before the step (a block of trace zero is set to
-    zero) and both 1-RDMs are contracted from the new 2-RDM.  ``sigma_so``
+    the same stopping rules and the three step controls (QUADRATIC with its
+    slope from ``norm_slope_spin``); each block is rescaled to its own trace
+    before the step (a block of trace zero is set to zero) and both 1-RDMs are
+    contracted from the new 2-RDM.  ``sigma_so``
     (2r reference occupations, alpha orbitals first) selects the NY 3-RDM of
     Eq. (8) in both maps; None is Valdemoro.  Returns a dict with ga, gb,
     d2aa, d2bb, d2ab of the returned state and the fields of ``euler``."""
-    if control not in (FIXED, BACKTRACK):
-        raise ValueError("the spin-block iteration takes the FIXED or BACKTRACK control")
+    if control not in (FIXED, BACKTRACK, QUADRATIC):
+        raise ValueError("unknown step control")
+    eps_max = eps_max if eps_max > 0.0 else 16.0 * abs(eps)
     h = np.asarray(h, dtype=np.float64)
     V = np.asarray(V, dtype=np.float64)
     r = h.shape[0]
@@ -221,8 +247,16 @@ def euler_spin(h, V, Na, Nb, ga, gb, d2aa, d2bb, d2ab, eps=1e-3, de_tol=1e-6, ma
         trials = [run(e)]
         chosen = trials[0] if (trials[0]["E"] <= E and trials[0]["f"] <= f) else None
         cand = e
+        if control == QUADRATIC:
+            g0 = norm_slope_spin(h, V, Na, Nb, ga, gb, *blocks, *ublocks, sigma_so=sigma_so)
+            x = quadratic_trial_step(f, g0, e, trials[0]["f"], eps_max)
+            if x is not None:
+                trials.append(run(x))
+                good = [q for q in trials if q["E"] <= E and q["f"] <= f]
+                chosen = min(good, key=lambda q: q["f"]) if good else None  # first on a tie
+                cand = min(e, x)
         halvings = 0
-        while chosen is None and control == BACKTRACK and halvings < max_halvings:
+        while chosen is None and control != FIXED and halvings < max_halvings:
             cand = 0.5 * cand
             halvings += 1
             t = run(cand)

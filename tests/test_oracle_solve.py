@@ -210,6 +210,83 @@ def test_euler_spin_on_singlet_inputs_is_the_singlet_iteration():
             assert np.abs(g[k] - ref).max() < 1e-12 * max(1.0, np.abs(ref).max()), k
 
 
+def _spin_line(ny):
+    """An open-shell state with its 1-RDMs contracted from its 2-RDM, the
+    update direction U of its step and f(s) = ||R(2D + s U, 1D + s dD)||^2."""
+    p = gen.spin_problem(5, 3, 1, 10, seed=2)
+    z = np.zeros((5, 5))
+    _, d2 = rdm.spin_blocks_to_spin_orbital(z, z, p["d2aa"], p["d2bb"], p["d2ab"])
+    g = rdm.contract_to_1rdm(d2, 4)
+    ga, gb = g[:5, :5].copy(), g[5:, 5:].copy()
+    sig = ost.sigma_open_shell(5, 3, 1) if ny else None
+    blocks = (p["d2aa"], p["d2bb"], p["d2ab"])
+    o = ost.step_spin(p["h"], p["V"], 3, 1, ga, gb, *blocks, 0.0, sigma_so=sig)
+    U = (o["U_aa"], o["U_bb"], o["U_ab"])
+    _, u2 = rdm.spin_blocks_to_spin_orbital(z, z, *U)
+    u1 = rdm.contract_to_1rdm(u2, 4)
+
+    def R(s):
+        bl = [b + s * u for b, u in zip(blocks, U)]
+        return ost.residual_spin(p["h"], p["V"], 3, 1, ga + s * u1[:5, :5], gb + s * u1[5:, 5:], *bl, sigma_so=sig)
+
+    return p, ga, gb, blocks, U, sig, R
+
+
+@pytest.mark.parametrize("ny", [False, True])
+def test_norm_slope_spin_matches_finite_differences(ny):
+    """The open-shell slope (autograd along the line) against central
+    differences of the numpy forward's ||R||^2."""
+    from oracle import solve as sv
+    p, ga, gb, blocks, U, sig, R = _spin_line(ny)
+    g0 = sv.norm_slope_spin(p["h"], p["V"], 3, 1, ga, gb, *blocks, *U, sigma_so=sig)
+    h = 1e-6
+    fd = (R(h)[3] - R(-h)[3]) / (2 * h)
+    assert abs(g0 - fd) <= 1e-8 * abs(fd)
+
+
+@pytest.mark.parametrize("ny", [False, True])
+def test_residual_is_quartic_along_a_line(ny):
+    """Along a straight line in (2D, 1D) the residual is a polynomial of degree
+    at most 4 in the line parameter (the Valdemoro 3-RDM cubic, the NY one
+    quartic in the RDMs): the five-point central difference of R at a large
+    step equals the exact directional derivative (the autograd slope), while
+    the three-point one (exact to degree 2) does not."""
+    from oracle import solve as sv
+    p, ga, gb, blocks, U, sig, R = _spin_line(ny)
+    g0 = sv.norm_slope_spin(p["h"], p["V"], 3, 1, ga, gb, *blocks, *U, sigma_so=sig)
+    H = 0.3
+    R0 = R(0.0)[:3]
+    Rh, Rm, R2h, R2m = (R(x)[:3] for x in (H, -H, 2 * H, -2 * H))
+    w = (1.0, 1.0, 4.0)  # spin-orbital norm weights of the aa, bb, ab blocks
+
+    def slope(d):
+        return 2.0 * sum(c * float(np.sum(a * b)) for c, a, b in zip(w, R0, d))
+    five = slope([(8.0 * (a - b) - (c - e)) / (12.0 * H) for a, b, c, e in zip(Rh, Rm, R2h, R2m)])
+    three = slope([(a - b) / (2.0 * H) for a, b in zip(Rh, Rm)])
+    assert abs(five - g0) <= 1e-12 * abs(g0)
+    assert abs(three - g0) > 1e-6 * abs(g0)
+
+
+def test_euler_spin_quadratic_on_singlet_inputs_is_the_singlet_iteration():
+    """The quadratic control of the spin-block iteration (its slope by
+    autograd along the line) on a singlet given as three blocks takes the
+    singlet iteration's trials (slope from the singlet adjoint)."""
+    from oracle import solve as sv
+    p = gen.problem(5, 4, 10, seed=3)
+    _, d2 = rdm.blocks_to_spin_orbital(np.eye(5), p["d2aa"], p["d2ab"])
+    g1 = rdm.contract_to_1rdm(d2, 4)[:5, :5]
+    s = sv.euler(p["h"], p["V"], 4, g1, p["d2aa"], p["d2ab"], eps=1e-2, de_tol=0.0, max_iter=3,
+                 control=sv.QUADRATIC, max_halvings=4)
+    g = sv.euler_spin(p["h"], p["V"], 2, 2, g1, g1, p["d2aa"], p["d2aa"], p["d2ab"], eps=1e-2, de_tol=0.0,
+                      max_iter=3, control=sv.QUADRATIC, max_halvings=4)
+    assert len(s["trials"]) > s["iterations"]  # a second (interpolated) trial was taken
+    assert g["stop"] == s["stop"] and g["iterations"] == s["iterations"]
+    assert len(g["trials"]) == len(s["trials"])
+    for a, b in zip(g["trials"], s["trials"]):
+        assert abs(a[0] - b[0]) <= 1e-9 * abs(b[0]) and a[3:] == b[3:]
+        assert abs(a[1] - b[1]) < 1e-10 * abs(b[1]) and abs(a[2] - b[2]) < 1e-10 * b[2]
+
+
 @pytest.mark.parametrize("ny", [False, True])
 def test_euler_spin_steps_are_step_spin_steps(ny):
     """Every accepted fixed-eps step of the spin-block iteration is one
