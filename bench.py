@@ -246,7 +246,8 @@ def bench_solve(acse, ctx, prob, work, pristine, torch, controls, iters, eps, st
 
 def bench_solve_spin(acse, ctx, gen, torch, controls, iters, eps, step_ms, name="r50s"):
     """acse_solve_spin (the Euler iteration for a state of any S_z, FP64) with
-    the fixed and backtracking controls on the open-shell workload, each from
+    the fixed, backtracking and quadratic controls (the last with its slope
+    from four more residual maps per step) on the open-shell workload, each from
     the state whose 1-RDMs are contracted from its 2-RDM (one acse_step_spin
     with eps = 0): wall time per accepted step and per map against the plain
     acse_step_spin time."""
@@ -261,8 +262,6 @@ def bench_solve_spin(acse, ctx, gen, torch, controls, iters, eps, step_ms, name=
     opts = acse.Context.options("fp64")
     res = {}
     for control in controls:
-        if control not in ("fixed", "backtrack"):
-            continue
         for w, q in zip(work, pristine):
             w.copy_(q)
         ctx.step_spin_raw(prob, 0.0, opts, want=False)

@@ -514,13 +514,21 @@ acse_status acse_step_spin(acse_ctx ctx, acse_problem_spin *prob, double eps, co
  * rules) for a state of any S_z: each trial is the step of acse_step_spin at
  * its step size from the kept state 2D_n (every block at 2D_n's block trace,
  * both 1-RDMs contracted from the new 2-RDM), its E and ||R||^2 as for
- * acse_residual_spin.  Controls ACSE_EULER_FIXED and ACSE_EULER_BACKTRACK;
- * ACSE_EULER_QUADRATIC is ACSE_ERR_UNSUPPORTED (it needs an adjoint of the
- * spin-block map).  prob's d1a, d1b, d2aa, d2bb and d2ab are overwritten with
- * the returned state; a rise returns the state before it.  opts, result,
- * history and capacity as for acse_solve and acse_step_spin (ACSE_FP64 or
- * ACSE_INT8CRT).  The first call allocates 3 r_max^4 + 2 r_max^2 doubles more
- * (the kept state), kept until acse_destroy.  Synchronises once per trial.
+ * acse_residual_spin.  The three controls of acse_solve; for
+ * ACSE_EULER_QUADRATIC the slope f'(0) of ||R||^2 along the step comes from
+ * the residual's derivative along the straight line (2D_n + x U_n, 1D_n + x dD),
+ * dD the 1-RDMs contracted from U_n: R is a polynomial of degree at most 4 in
+ * x there (the 3-RDM of either reconstruction is at most quartic in the
+ * RDMs), so the five-point central difference at x = +-eps, +-2eps is exact up
+ * to rounding (four more residual maps per step, counted in result->maps;
+ * the trace restoration leaves the slope unchanged since Tr U_n = 0 per
+ * block).  prob's d1a, d1b, d2aa, d2bb and d2ab are overwritten with the
+ * returned state; a rise returns the state before it.  opts, result, history
+ * and capacity as for acse_solve and acse_step_spin (ACSE_FP64 or
+ * ACSE_INT8CRT, either reconstruction).  The first call allocates
+ * 3 r_max^4 + 2 r_max^2 doubles more (the kept state), the first quadratic
+ * one 6 r_max^4 + 2 r_max^2 more, kept until acse_destroy.  Synchronises once
+ * per trial and once per slope.
  * On an error mid-run the problem arrays hold the last accepted or trial
  * state. */
 acse_status acse_solve_spin(acse_ctx ctx, acse_problem_spin *prob, const acse_options *opts,

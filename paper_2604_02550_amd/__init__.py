@@ -534,13 +534,13 @@ class Context:
 
     def solve_spin(self, h, V, d1a, d1b, d2aa, d2bb, d2ab, n_alpha, n_beta, eps=1e-3, de_tol=1e-6,
                    max_iter=100, control="fixed", max_halvings=8, precision="fp64", active=None, tile=-1,
-                   flags=0, capacity=256, moduli=0, sigma=None):
+                   flags=0, capacity=256, moduli=0, sigma=None, eps_max=0.0):
         """The Euler iteration of ``solve`` for a state of any S_z on device
-        copies of the inputs (acse_solve_spin; controls "fixed" and
-        "backtrack").  Returns a dict with the final d1a, d1b, d2aa, d2bb, d2ab
-        (device) and the fields of ``solve``."""
+        copies of the inputs (acse_solve_spin; controls "fixed", "backtrack"
+        and "quadratic").  Returns a dict with the final d1a, d1b, d2aa, d2bb,
+        d2ab (device) and the fields of ``solve``."""
         prob, t = self.problem_spin(h, V, d1a, d1b, d2aa, d2bb, d2ab, n_alpha, n_beta)
-        so = SolveOptions(float(eps), float(de_tol), 0.0, int(max_iter),
+        so = SolveOptions(float(eps), float(de_tol), float(eps_max), int(max_iter),
                           CONTROLS[control] if isinstance(control, str) else int(control), int(max_halvings), 0)
         res, hist = self.solve_spin_raw(prob, self.options(precision, active, tile, flags, sigma, moduli), so,
                                         capacity)

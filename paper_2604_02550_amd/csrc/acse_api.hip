@@ -3046,6 +3046,10 @@ struct SpinWs {
   // (allocated by the first acse_solve_spin call)
   void *kbase = nullptr;
   double *Nk[3] = {}, *gk[2] = {};
+  // the quadratic control's slope (allocated by its first use): R_n kept, the
+  // five-point combination of the residuals along the line, the 1-RDMs of U
+  void *qbase = nullptr;
+  double *Rk[3] = {}, *Qa[3] = {}, *dg[2] = {};
 };
 
 acse_status ensure_spin_ws(acse_ctx c, SpinWs *&out) {
@@ -3766,13 +3770,25 @@ extern "C" acse_status acse_solve_spin(acse_ctx ctx, acse_problem_spin *prob, co
   acse_status st = validate_spin(ctx, prob, opts, true);
   if (st != ACSE_OK) return st;
   if ((st = check_solve_options(ctx, so, res, hist, cap)) != ACSE_OK) return st;
-  if (so->control == ACSE_EULER_QUADRATIC)
-    return fail(ctx, ACSE_ERR_UNSUPPORTED, "the spin-block iteration takes the FIXED or BACKTRACK control (the "
-                                           "quadratic control needs an adjoint of the spin-block map)");
+  const bool quad = so->control == ACSE_EULER_QUADRATIC;
+  const double eps_max = so->eps_max > 0.0 ? so->eps_max : 16.0 * std::fabs(so->eps);
   HIP_TRY(ctx, hipSetDevice(ctx->device));
   SpinWs *wp = nullptr;
   if ((st = ensure_spin_ws(ctx, wp)) != ACSE_OK) return st;
   SpinWs &w = *wp;
+  if (quad && !w.qbase) {
+    const int64_t rm2 = (int64_t)ctx->r_max * ctx->r_max;
+    const int64_t nat = round_up(rm2 * rm2 * 8, 256), sm = round_up(rm2 * 8, 256);
+    if (hipMalloc(&w.qbase, 6 * nat + 2 * sm) != hipSuccess) {
+      (void)hipGetLastError();
+      w.qbase = nullptr;
+      return fail(ctx, ACSE_ERR_NOMEM, "cannot allocate the workspace of the quadratic control");
+    }
+    char *q = static_cast<char *>(w.qbase);
+    for (int k = 0; k < 3; ++k, q += nat) w.Rk[k] = reinterpret_cast<double *>(q);
+    for (int k = 0; k < 3; ++k, q += nat) w.Qa[k] = reinterpret_cast<double *>(q);
+    for (int k = 0; k < 2; ++k, q += sm) w.dg[k] = reinterpret_cast<double *>(q);
+  }
   if (ctx->crt_moduli && (st = ensure_spin_crt(ctx, w)) != ACSE_OK) return st;
   if (!w.kbase) {
     const int64_t rm2 = (int64_t)ctx->r_max * ctx->r_max;
@@ -3866,15 +3882,70 @@ extern "C" acse_status acse_solve_spin(acse_ctx ctx, acse_problem_spin *prob, co
       const double *tr_in[6] = {d2[0], d2[1], d2[2], w.U[0], w.U[1], w.U[2]};
       HIP_TRY(ctx, launch_pair_traces(r, 6, tr_in, traces, s));
     }
+    // f'(0) of f(x) = ||R(2D_n + x U_n, 1D_n + x dD)||^2, dD the 1-RDMs
+    // contracted from U_n: along this line R is a polynomial of degree at
+    // most 4 in x (the 3-RDM is at most quartic in the RDMs), so the
+    // five-point central difference of R at x = +-h, +-2h (h = eps) is its
+    // exact derivative up to rounding; f'(0) = 2 <R_n, R'(0)> over spin
+    // orbitals.  The trace restoration of the trials leaves the slope
+    // unchanged (Tr U_n = 0 per block).
+    double g0 = 0.0;
+    if (quad) {
+      for (int k = 0; k < 3; ++k) {
+        HIP_TRY(ctx, hipMemcpyAsync(w.Rk[k], w.R[k], n4 * 8, hipMemcpyDeviceToDevice, s));
+        HIP_TRY(ctx, launch_fill(n4, 0.0, w.Qa[k], s));
+      }
+      HIP_TRY(ctx, launch_spin_1rdm(r, N, w.U[0], w.U[1], w.U[2], w.dg[0], w.dg[1], s));
+      const double h = e;
+      const double xs[4] = {h, -h, 2.0 * h, -2.0 * h}, cw[4] = {8.0, -8.0, -1.0, 1.0};
+      for (int q = 0; q < 4; ++q) {
+        for (int k = 0; k < 3; ++k) HIP_TRY(ctx, launch_spin_axpy(n4, w.Nk[k], xs[q], w.U[k], d2[k], s));
+        for (int k = 0; k < 2; ++k) HIP_TRY(ctx, launch_spin_axpy(r2, w.gk[k], xs[q], w.dg[k], d1[k], s));
+        double fq = 0.0, Eq = 0.0;
+        if ((st = residual(&fq, &Eq)) != ACSE_OK) return st;
+        for (int k = 0; k < 3; ++k) HIP_TRY(ctx, launch_spin_axpy(n4, w.Qa[k], cw[q], w.R[k], w.Qa[k], s));
+      }
+      for (int k = 0; k < 3; ++k) HIP_TRY(ctx, launch_dot(n4, w.Rk[k], w.Qa[k], w.part, w.scal + 32 + k, s));
+      double dots[3];
+      HIP_TRY(ctx, hipMemcpyAsync(dots, w.scal + 32, sizeof dots, hipMemcpyDeviceToHost, s));
+      HIP_TRY(ctx, hipStreamSynchronize(s));
+      g0 = 2.0 * (dots[0] + dots[1] + 4.0 * dots[2]) / (12.0 * h);
+      if (!std::isfinite(g0)) return fail(ctx, ACSE_ERR_NONFINITE, "slope of ||R||^2 is not finite");
+    }
 
     auto ok = [&](double Et, double ft) { return Et <= E && ft <= f; };
-    double xc = e, fc = 0.0, Ec = 0.0;
-    if ((st = trial(xc, false, &fc, &Ec)) != ACSE_OK) return st;
+    const double x1 = e;
+    double xc = x1, fc = 0.0, Ec = 0.0;
+    // the slope's evaluations left the line's last point in the arrays
+    if ((st = trial(xc, quad, &fc, &Ec)) != ACSE_OK) return st;
     int32_t idc = record(xc, Ec, fc, n);
+    const double f1 = fc, E1 = Ec;
+    const int32_t id1 = idc;
     bool chosen = ok(Ec, fc);
     double last_E = Ec;
     double cand = e;
-    for (int hv = 0; !chosen && so->control == ACSE_EULER_BACKTRACK && hv < so->max_halvings; ++hv) {
+    if (quad) {
+      const double x2 = quadratic_second_step(f, g0, x1, f1, eps_max);
+      if (x2 != 0.0) {
+        double f2 = 0.0, E2 = 0.0;
+        if ((st = trial(x2, true, &f2, &E2)) != ACSE_OK) return st;
+        const int32_t id2 = record(x2, E2, f2, n);
+        last_E = E2;
+        const bool ok1 = ok(E1, f1), ok2 = ok(E2, f2);
+        if (ok2 && (!ok1 || f2 < f1)) {
+          chosen = true; xc = x2; fc = f2; Ec = E2; idc = id2;
+        } else if (ok1) {
+          // the arrays hold the second trial: evaluate the first again (same kernels, same values)
+          double fr = 0.0, Er = 0.0;
+          if ((st = trial(x1, true, &fr, &Er)) != ACSE_OK) return st;
+          chosen = true; xc = x1; fc = f1; Ec = E1; idc = id1;
+        } else {
+          chosen = false;
+        }
+        cand = std::min(x1, x2);
+      }
+    }
+    for (int hv = 0; !chosen && so->control != ACSE_EULER_FIXED && hv < so->max_halvings; ++hv) {
       cand *= 0.5;
       double ft = 0.0, Et = 0.0;
       if ((st = trial(cand, true, &ft, &Et)) != ACSE_OK) return st;
@@ -3911,6 +3982,7 @@ void release_spin_ws(acse_ctx c) {
   SpinWs *w = static_cast<SpinWs *>(c->spws);
   if (w && w->cbase) (void)hipFree(w->cbase);
   if (w && w->kbase) (void)hipFree(w->kbase);
+  if (w && w->qbase) (void)hipFree(w->qbase);
   delete w;
   c->spws = nullptr;
 }

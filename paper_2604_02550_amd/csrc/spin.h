@@ -53,6 +53,9 @@ hipError_t launch_unpack_rows_lt(int r, const double *C, int64_t ldc, double *ou
 hipError_t launch_spin_1rdm(int r, int N, const double *d2aa, const double *d2bb, const double *d2ab, double *ga,
                             double *gb, hipStream_t s);
 
+// out = x + c y over n elements (out may be x).
+hipError_t launch_spin_axpy(int64_t n, const double *x, double c, const double *y, double *out, hipStream_t s);
+
 // ---- spin-orbital tensors of the NY share (n = 2r spin orbitals, alpha
 // orbitals first: spin orbital p + r sigma) ------------------------------------
 // Spin-block (bits b, bit 3 - t set when index t is beta) of a natural n^4

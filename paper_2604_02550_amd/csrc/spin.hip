@@ -462,6 +462,12 @@ k_so_d1bar_singlet(int r, const double *__restrict__ g, const double *__restrict
   if (threadIdx.x == 0) gb[blockIdx.x] += -0.5 * (((part[0] + part[1]) + part[2]) + part[3]);
 }
 
+__global__ void __launch_bounds__(256)
+k_spin_axpy(int64_t n, const double *x, double c, const double *__restrict__ y, double *out) {
+  const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (e < n) out[e] = x[e] + c * y[e];
+}
+
 inline dim3 grid1(int64_t n) { return dim3((unsigned)((n + 255) / 256)); }
 
 }  // namespace
@@ -508,6 +514,11 @@ hipError_t launch_spin_update(int r, double eps, double *const *d2, const double
 
 hipError_t launch_unpack_rows_lt(int r, const double *C, int64_t ldc, double *out, hipStream_t s) {
   hipLaunchKernelGGL(k_unpack_rows_lt, grid1((int64_t)r * r * r * r), dim3(256), 0, s, r, C, ldc, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_spin_axpy(int64_t n, const double *x, double c, const double *y, double *out, hipStream_t s) {
+  hipLaunchKernelGGL(k_spin_axpy, grid1(n), dim3(256), 0, s, n, x, c, y, out);
   return hipGetLastError();
 }
 

@@ -15,6 +15,7 @@ import pytest
 from oracle import fermion as fm
 from oracle import rdm
 from oracle import solve as osv
+from oracle import step as ost
 from synth import generators as gen
 
 pytestmark = pytest.mark.gpu
@@ -162,8 +163,9 @@ def test_solve_spin_on_singlet_inputs_matches_singlet_solve(ctx):
 
 
 def test_solve_spin_zero_steps_and_refusals(acse, ctx):
-    """max_iter = 0 evaluates the input state only and leaves it unchanged; the
-    quadratic control, unsupported precisions and bad options are refused."""
+    """max_iter = 0 evaluates the input state only and leaves it unchanged;
+    unsupported precisions and bad options (an uphill step size for the
+    quadratic control) are refused."""
     p = consistent(gen.spin_problem(6, 4, 2, 12, seed=1))
     args = (p["h"], p["V"], p["gamma_a"], p["gamma_b"], p["d2aa"], p["d2bb"], p["d2ab"], 4, 2)
     g = ctx.solve_spin(*args, eps=1e-2, max_iter=0)
@@ -173,11 +175,78 @@ def test_solve_spin_zero_steps_and_refusals(acse, ctx):
         assert np.array_equal(cpu(g[k]), p[k]), k
     e0 = ctx.energy_spin(p["h"], p["V"], p["d2aa"], p["d2bb"], p["d2ab"], 4, 2)
     assert abs(g["energy0"] - e0) <= TOL * max(1.0, abs(e0))
-    with pytest.raises(acse.AcseError, match="UNSUPPORTED"):
-        ctx.solve_spin(*args, control="quadratic")
+    with pytest.raises(acse.AcseError, match="ARG"):
+        ctx.solve_spin(*args, control="quadratic", eps=-1e-2)
     with pytest.raises(acse.AcseError, match="UNSUPPORTED"):
         ctx.solve_spin(*args, precision="fp32")
     with pytest.raises(acse.AcseError, match="ARG"):
         ctx.solve_spin(*args, eps=0.0)
     with pytest.raises(acse.AcseError, match="ARG"):
         ctx.solve_spin(*args, max_halvings=61, control="backtrack")
+
+
+# (problem, first step size, NY, precision): interpolated second trials that
+# are taken, first trials kept after a second one (evaluated again), rejected
+# first trials; every decision clears its threshold by 2.9e-4 relative or more
+QUAD_CASES = {
+    "r6": (lambda: consistent(gen.spin_problem(6, 4, 2, 12, seed=1)), 1e-2, False, "fp64"),
+    "fock": (lambda: fock_problem(4, 3, 1, 2), 0.05, False, "fp64"),
+    "fock_ny": (lambda: fock_problem(4, 3, 1, 2), 0.05, True, "fp64"),
+    "r9_int8crt": (lambda: consistent(gen.spin_problem(9, 5, 4, 18, seed=2)), 1e-3, False, "int8crt"),
+    "r6_ny": (lambda: consistent(gen.spin_problem(6, 4, 2, 12, seed=1)), 1e-2, True, "fp64"),
+}
+
+
+@pytest.mark.parametrize("name", list(QUAD_CASES))
+def test_solve_spin_quadratic_matches_oracle_iteration(ctx, name):
+    """The quadratic control for states of any S_z: the GPU takes f'(0) from the
+    five-point central difference of R along the step (exact for the residual's
+    polynomial dependence on the step), the oracle by autograd.  The second
+    step size is a ratio of differences (two digits lost to cancellation), so
+    the step sizes are compared at 1e-7 and the scalars and arrays at 1e-8, as
+    for the singlet quadratic control."""
+    make, eps, ny, precision = QUAD_CASES[name]
+    p = make()
+    r = p["h"].shape[0]
+    sig = ost.sigma_open_shell(r, p["Na"], p["Nb"]) if ny else None
+    print(f"[solve_spin quadratic] {name}", flush=True)
+    o = osv.euler_spin(p["h"], p["V"], p["Na"], p["Nb"], p["gamma_a"], p["gamma_b"], p["d2aa"], p["d2bb"],
+                       p["d2ab"], eps=eps, de_tol=0.0, max_iter=4, control=osv.QUADRATIC, max_halvings=6,
+                       sigma_so=sig)
+    g = ctx.solve_spin(p["h"], p["V"], p["gamma_a"], p["gamma_b"], p["d2aa"], p["d2bb"], p["d2ab"], p["Na"],
+                       p["Nb"], eps=eps, de_tol=0.0, max_iter=4, control="quadratic", max_halvings=6,
+                       precision=precision, sigma=True if ny else None)
+    assert g["stop"] == STOPS[o["stop"]]
+    assert g["iterations"] == o["iterations"]
+    assert g["trial_count"] == len(o["trials"])
+    # per step: U, four residuals along the line, one per trial (and one more
+    # when a first trial is kept after a second)
+    steps = len({t[3] for t in o["trials"]})
+    assert g["maps"] >= 1 + 5 * steps + len(o["trials"])
+    for a, b in zip(g["trials"], o["trials"]):
+        assert a[3] == b[3] and a[4] == b[4]
+        assert abs(a[0] - b[0]) <= 1e-7 * abs(b[0])
+        assert abs(a[1] - b[1]) <= 1e-8 * max(1.0, abs(b[1]))
+        assert abs(a[2] - b[2]) <= 1e-8 * b[2]
+    scale = max(np.abs(o[k]).max() for k in ("d2aa", "d2bb", "d2ab"))
+    for k in ("d2aa", "d2bb", "d2ab"):
+        assert np.abs(cpu(g[k]) - o[k]).max() <= 1e-8 * scale, k
+
+
+def test_solve_spin_quadratic_on_singlet_inputs_matches_singlet_solve(ctx):
+    """On a singlet given as three blocks, the spin-block quadratic control
+    (slope from the five-point difference along the line) takes the trials of
+    the singlet quadratic control (slope from the hand-written adjoint)."""
+    p = gen.problem(5, 4, 10, seed=3)
+    g1 = consistent(dict(p, Na=2, Nb=2, d2bb=p["d2aa"]))["gamma_a"]
+    print("[solve_spin quadratic] singlet inputs r5", flush=True)
+    kw = dict(eps=1e-2, de_tol=0.0, max_iter=3, control="quadratic", max_halvings=4)
+    g = ctx.solve_spin(p["h"], p["V"], g1, g1, p["d2aa"], p["d2aa"], p["d2ab"], 2, 2, **kw)
+    s = ctx.solve(p["h"], p["V"], g1, p["d2aa"], p["d2ab"], 2, **kw)
+    assert len(s["trials"]) > s["iterations"]  # second (interpolated) trials were taken
+    assert g["stop"] == s["stop"] and g["iterations"] == s["iterations"]
+    assert len(g["trials"]) == len(s["trials"])
+    for a, b in zip(g["trials"], s["trials"]):
+        assert a[3:] == b[3:]
+        assert abs(a[0] - b[0]) <= 1e-7 * abs(b[0])
+        assert abs(a[1] - b[1]) <= 1e-8 * abs(b[1]) and abs(a[2] - b[2]) <= 1e-8 * b[2]
