@@ -260,6 +260,28 @@ def test_r30_mixed_precision_errors(ctx, r30, precision):
     assert de_rel < tol["dE_rel"]
 
 
+@pytest.mark.parametrize("tile", [0, 1, 2])
+@pytest.mark.parametrize("name", ["r6", "r13", "r30"])
+def test_bf16x3_every_tile_config(ctx, r30, name, tile):
+    """Every split-BF16 tile configuration against the FP64 oracle at the
+    split-BF16 tolerances.  Configuration 2 is the 256 x 256 direct-load
+    kernel, whose edge tiles read clamped rows: one tile at r^2 = 36, one
+    with a ragged edge at 169, four with a 132-row tail at 900."""
+    if name == "r30":
+        p, o = r30
+    else:
+        p = PROBLEMS[name]()
+        o = ost.step(p["h"], p["V"], p["N"], p["gamma"], p["d2aa"], p["d2ab"], 1e-3)
+    print(f"[bf16x3 tile] {name} tile={tile}", flush=True)
+    g = ctx.step(p["h"], p["V"], p["gamma"], p["d2aa"], p["d2ab"], p["N"] // 2, eps=1e-3,
+                 precision="bf16x3", tile=tile, return_ru=True)
+    tol = MIXED_TOL["bf16x3"]
+    for key, t in (("R_aa", tol["R"]), ("R_ab", tol["R"]), ("U_aa", tol["U"]), ("U_ab", tol["U"])):
+        assert rel(cpu(g[key]), o[key]) < t, key
+        assert maxrel(cpu(g[key]), o[key]) < 10 * t, key
+    assert abs(g["energy"] - o["energy"]) <= tol["dE_rel"] * abs(o["energy"] - o["energy0"])
+
+
 def test_input_symmetry_check(acse, ctx):
     """ACSE_FLAG_CHECK_INPUTS: symmetric inputs pass and give the same residual
     bitwise; a planted violation in each input array is reported by name."""
