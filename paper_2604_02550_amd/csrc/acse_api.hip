@@ -799,14 +799,24 @@ acse_status ny_share_run(acse_ctx c, const acse_problem *p, GemmPrec prec, int t
       HIP_TRY(c, launch_permute4(prec, a, opref(o.buf), s));
     }
     // int8 products: the residues of every operand buffer this phase reads
-    // (K = r^2, or the r(r-1)/2 pairs of a packed operand)
+    // (K = r^2, or the r(r-1)/2 pairs of a packed operand); those of the
+    // buffers built from D and sigma D alone are kept from the previous map
+    // of the same step, like the buffers themselves (every buffer has its own
+    // residue planes, and both maps run with the same moduli)
     std::vector<int> buf_packed(P.num_bufs, 0);
-    for (const ny::OperandBuild &o : P.operands) buf_packed[o.buf] = o.packed;
+    std::vector<char> rdm_only(P.num_bufs, 0);
+    for (const ny::OperandBuild &o : P.operands) {
+      buf_packed[o.buf] = o.packed;
+      rdm_only[o.buf] = ny::is_source(o.t1) && o.t1 != ny::T_X;
+    }
     auto kdim = [&](int buf) { return buf_packed[buf] ? npair_lt(r) : (int)r2; };
     if (crt) {
       std::vector<char> used(P.num_bufs, 0);
       for (const ny::Product &g : P.products)
         if (g.phase == phase) used[g.a_buf] = used[g.b_buf] = 1;
+      if (keep_d)
+        for (int id = 0; id < P.num_bufs; ++id)
+          if (rdm_only[id]) used[id] = 0;
       ResidueBatch rb{};
       int nrows = 0;
       for (int id = 0; id <= P.num_bufs; ++id) {
