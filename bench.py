@@ -372,7 +372,8 @@ def bench_spin(acse, ctx, gen, torch, steps, warmup, eps, mode="fp64", name="r50
     ("int8crt").  Inputs restored from a pristine device copy inside the timed
     region.  Checked against the stored FP64 oracle values of the same step
     (Valdemoro).  With ``ny`` both maps add the NY share (default open-shell
-    occupations), FP64 over spin-orbital tensors (2r = 100)."""
+    occupations) over spin-orbital tensors (2r = 100), its block products in
+    the mode's precision."""
     dev = torch.device("cuda", 0)
     p = gen.named_spin(name)
     r = p["r"]
@@ -448,10 +449,13 @@ def bench_spin(acse, ctx, gen, torch, steps, warmup, eps, mode="fp64", name="r50
         ny_flops = 2 * 6 * 10 * 2 * r ** 6
         ny_ms, _ = prof["ny_share"]
         nyg_ms, _ = prof["ny_gemm"]
+        rate = ny_flops / (nyg_ms / steps * 1e-3) / 1e12  # FP64-equivalent rate of the block products
         extra = dict(ny_share_ms_per_step=ny_ms / steps, ny_gemm_ms_per_step=nyg_ms / steps,
-                     ny_gemm_flops_per_step=ny_flops,
-                     ny_gemm_tflops=ny_flops / (nyg_ms / steps * 1e-3) / 1e12,
-                     ny_gemm_frac_fp64=ny_flops / (nyg_ms / steps * 1e-3) / 1e12 / PEAK_TFLOPS["fp64"])
+                     ny_gemm_flops_per_step=ny_flops, ny_gemm_tflops=rate)
+        if mode == "int8crt":   # int8 ops: one product per modulus, against the int8 peak
+            extra["ny_gemm_frac_int8"] = rate * CRT_MODULI / PEAK_TFLOPS["int8crt"]
+        else:
+            extra["ny_gemm_frac_fp64"] = rate / PEAK_TFLOPS["fp64"]
     return dict(
         workload=f"{name}: r={r}, N_alpha={p['Na']}, N_beta={p['Nb']}, three 2-RDM spin blocks, one "
                  f"acse_step_spin (eps={eps}) per step, products {mode}"
@@ -693,8 +697,9 @@ def main():
         line["non_singlet"] = {m: bench_spin(acse, ctx, gen, torch, args.spin_steps, min(args.warmup, 2), args.eps, m)
                                for m in ("int8crt", "fp64")}
         if args.spin_ny_steps > 0:
-            line["non_singlet"]["ny_fp64"] = bench_spin(acse, ctx, gen, torch, args.spin_ny_steps, 1, args.eps,
-                                                        "fp64", ny=True)
+            for m in ("int8crt", "fp64"):
+                line["non_singlet"]["ny_" + m] = bench_spin(acse, ctx, gen, torch, args.spin_ny_steps, 1,
+                                                            args.eps, m, ny=True)
         if args.solve_controls:
             line["non_singlet"]["solve_fp64"] = bench_solve_spin(
                 acse, ctx, gen, torch, args.solve_controls.split(","), args.solve_iters, args.solve_eps,

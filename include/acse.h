@@ -468,13 +468,15 @@ acse_status acse_residual_noalloc(void *hip_stream, const acse_problem *prob, co
  * precisions are ACSE_ERR_UNSUPPORTED); tile as for acse_residual (FP64);
  * either reconstruction.  With ACSE_RECON_NY (r <= 64, otherwise
  * ACSE_ERR_UNSUPPORTED) the NY 3-cumulant of Eq. (8) joins both maps of a
- * step: its share runs in FP64 over spin-orbital tensors (n = 2r spin
- * orbitals; six pairwise contractions per map, each run as the 10 of its 64
- * r^2 x r^2 x r^2 spin-block products whose operand blocks conserve spin),
- * also under ACSE_INT8CRT; its first call allocates 6 n^4 doubles and two
- * operand buffers of 16 round_up(r^2, 256) round_up(r^2, 64) doubles for its
- * r (1.1 GB at r = 32, 6.5 GB at r = 50), reallocated when a larger r comes
- * and kept until acse_destroy.  The first call allocates a workspace for
+ * step: its share runs over spin-orbital tensors (n = 2r spin orbitals; six
+ * pairwise contractions per map, each run as the 10 of its 64 r^2 x r^2 x r^2
+ * spin-block products whose operand blocks conserve spin), the block
+ * products in FP64, or under ACSE_INT8CRT as int8 exact-accumulation
+ * products; its first call allocates 6 n^4 doubles and two operand buffers
+ * of 16 round_up(r^2, 256) round_up(r^2, 64) doubles for its r (1.1 GB at
+ * r = 32, 6.5 GB at r = 50), its first ACSE_INT8CRT call the residues of
+ * the 32 operand sub-blocks and of one launch's six products (3.7 GB at
+ * r = 50), reallocated when a larger r comes and kept until acse_destroy.  The first call allocates a workspace for
  * r_max: 48 r_max^4 doubles and 25 GEMM operand buffers (about 3.7 GB at
  * r_max = 50), kept until acse_destroy; the first ACSE_INT8CRT call adds the
  * residues of those buffers and of one launch's products (about 3.0 GB at

@@ -1477,7 +1477,16 @@ struct SoWs {
   double *opA = nullptr, *opB = nullptr, *Y = nullptr, *Yb = nullptr, *sig = nullptr;
   std::vector<double> sig_host;  // what sig holds
   int op_r = 0;                  // r whose operand layout the padding of opA / opB was cleared for
+  // int8 products (ACSE_INT8CRT): residue planes and row exponents of each of
+  // the 16 (row spin pair, summed spin pair) sub-blocks of opA and opB, and
+  // the residues of one launch's products; sized for c_r orbitals
+  void *cbase = nullptr;
+  int c_r = 0;
+  int8_t *cres[2][16] = {};
+  int *cexp[2][16] = {};
+  int8_t *cy = nullptr;
 };
+constexpr int kSoCrtProbs = 6;  // products per modular launch
 
 // Spin-blocked operand of r spatial orbitals: 4 row blocks of rpad rows, 4
 // column chunks of kc columns (one per spin pair of the row / summed letters).
@@ -1526,8 +1535,43 @@ acse_status ensure_so_ws(acse_ctx c, int n, int narr, SoWs *&out) {
   return ACSE_OK;
 }
 
+// The residue workspace of the int8 spin-orbital products (first such call,
+// or a larger r).
+acse_status ensure_so_crt(acse_ctx c, SoWs &w, int r) {
+  if (w.cbase && w.c_r >= r) return ACSE_OK;
+  if (w.cbase) {
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    (void)hipFree(w.cbase);
+    w.cbase = nullptr;
+    w.c_r = 0;
+  }
+  const int64_t r2 = (int64_t)r * r, rpad = so_rpad(r);
+  const int64_t rbytes = round_up((int64_t)kMaxModuli * rpad * crt_ldr((int)r2), 256);
+  const int64_t ebytes = round_up(rpad * (int64_t)sizeof(int), 256);
+  const int64_t ybytes = round_up(kSoCrtProbs * (int64_t)kMaxModuli * crt_residue_out_bytes((int)r2, (int)r2), 256);
+  const int64_t bytes = 32 * (rbytes + ebytes) + ybytes;
+  if (hipMalloc(&w.cbase, bytes) != hipSuccess) {
+    (void)hipGetLastError();
+    w.cbase = nullptr;
+    return fail(c, ACSE_ERR_NOMEM, "cannot allocate the int8 residue workspace of the spin-orbital products (" +
+                                       std::to_string(bytes) + " bytes)");
+  }
+  char *q = static_cast<char *>(w.cbase);
+  for (int side = 0; side < 2; ++side)
+    for (int k = 0; k < 16; ++k) {
+      w.cres[side][k] = reinterpret_cast<int8_t *>(q);
+      q += rbytes;
+      w.cexp[side][k] = reinterpret_cast<int *>(q);
+      q += ebytes;
+    }
+  w.cy = reinterpret_cast<int8_t *>(q);
+  w.c_r = r;
+  return ACSE_OK;
+}
+
 void release_so_ws(acse_ctx c) {
   SoWs *w = static_cast<SoWs *>(c->sows);
+  if (w && w->cbase) (void)hipFree(w->cbase);
   if (w && w->base) (void)hipFree(w->base);
   delete w;
   c->sows = nullptr;
@@ -1564,9 +1608,15 @@ bool so_block_nonzero(int pair, const int sp[4]) {
 // r^2 x r^2 blocks); one r^2 x r^2 x r^2 FP64 product runs per output spin
 // block and summed spin pair whose A and B blocks both conserve spin, written
 // through 4-index store strides into its spin block of out.  Without acc the
-// output is cleared first (its blocks no product reaches stay zero).
+// output is cleared first (its blocks no product reaches stay zero).  crt:
+// the products run on the int8 matrix cores in exact accumulation (the
+// moduli of the call in progress): every operand sub-block a product reads
+// is converted to residues with one exponent per row over its K = r^2
+// columns, the products go out in launches of kSoCrtProbs, and each launch's
+// reconstruction writes through the same store strides.
 acse_status so_contract(acse_ctx c, SoWs &w, int n, double *out, const char *lo, const double *A, const char *la,
-                        int pa, const double *B, const char *lb, int pb, double alpha, int acc = 0) {
+                        int pa, const double *B, const char *lb, int pb, double alpha, int acc = 0,
+                        bool crt = false) {
   auto pos = [](const char *t, char ch) {
     for (int k = 0; k < 4; ++k)
       if (t[k] == ch) return k;
@@ -1628,6 +1678,92 @@ acse_status so_contract(acse_ctx c, SoWs &w, int n, double *out, const char *lo,
   const int kp = gemm_kp(GEMM_F64, (int)r2, (int)kc);
   const int64_t sm1 = pw[pos(lo, fa[0])], sm0 = pw[pos(lo, fa[1])];
   const int64_t sn1 = pw[pos(lo, fb[0])], sn0 = pw[pos(lo, fb[1])];
+  if (crt) {
+    acse_status st = ensure_so_crt(c, w, r);
+    if (st != ACSE_OK) return st;
+    const int K = (int)r2;
+    const int64_t ldr = crt_ldr(K), plane = rpad * ldr, plane_y = crt_residue_out_bytes(K, K);
+    const int kbits = crt_kbits(c->crt, K);
+    bool need[2][16] = {};
+    for (int RS = 0; RS < 4; ++RS)
+      for (int CS = 0; CS < 4; ++CS)
+        for (int t = 0; t < cnt[RS][CS]; ++t) {
+          need[0][RS * 4 + ks[RS][CS][t]] = true;
+          need[1][CS * 4 + ks[RS][CS][t]] = true;
+        }
+    ResidueBatch rb{};
+    int nrows = 0;
+    for (int side = 0; side < 2; ++side)
+      for (int q = 0; q < 16; ++q) {
+        if (!need[side][q]) continue;
+        if (rb.count == kMaxResidueJobs) {
+          rb.total_rows = nrows;
+          HIP_TRY(c, launch_to_residues(rb, c->crt, s));
+          rb = ResidueBatch{};
+          nrows = 0;
+        }
+        ResidueJob &J = rb.job[rb.count++];
+        J.src = (side ? w.opB : w.opA) + (q >> 2) * rpad * ld + (q & 3) * kc;
+        J.dst = w.cres[side][q];
+        J.e = w.cexp[side][q];
+        J.plane = plane;
+        J.row_begin = nrows;
+        J.K = K;
+        J.ld = (int)ld;
+        J.ldr = (int)ldr;
+        J.kbits = kbits;
+        J.premul = 0;
+        nrows += K;
+      }
+    if (rb.count) {
+      rb.total_rows = nrows;
+      HIP_TRY(c, launch_to_residues(rb, c->crt, s));
+    }
+    // round t: the t-th summed spin pair of every output block; a launch never
+    // spans two rounds, so that no launch holds two products of one output
+    for (int t = 0; t < 4; ++t) {
+      GemmBatch b{};
+      b.count = 0;
+      for (int RS = 0; RS < 4; ++RS)
+        for (int CS = 0; CS < 4; ++CS) {
+          if (cnt[RS][CS] <= t) continue;
+          const int KS = ks[RS][CS][t];
+          GemmProb &P = b.p[b.count];
+          P = GemmProb{};
+          P.A = w.cres[0][RS * 4 + KS];
+          P.B = w.cres[1][CS * 4 + KS];
+          P.C = out + (RS >> 1) * r * sm1 + (RS & 1) * r * sm0 + (CS >> 1) * r * sn1 + (CS & 1) * r * sn0;
+          P.alpha = alpha;
+          P.M = K; P.N = K; P.ld = P.Kp = (int)ldr; P.rdiv = r;
+          P.sm1 = sm1; P.sm0 = sm0; P.sn1 = sn1; P.sn0 = sn0;
+          P.ksplit = 1; P.kchunk = P.Kp; P.accumulate = (t == 0 && !acc) ? 0 : 1;
+          P.plane_a = P.plane_b = plane;
+          P.ea = w.cexp[0][RS * 4 + KS];
+          P.eb = w.cexp[1][CS * 4 + KS];
+          P.kshift = 2 * kbits;
+          P.u_out = 1;
+          P.plane_y = plane_y;
+          P.Y = w.cy + (int64_t)b.count * c->crt.nmod * plane_y;
+          if (++b.count == kSoCrtProbs) {
+            {
+              StageTimer t7(c, 7);  // the modular products alone
+              HIP_TRY(c, gemm_crt_launch(b, c->crt, s));
+            }
+            HIP_TRY(c, crt_combine_launch(b, c->crt, s));
+            b = GemmBatch{};
+            b.count = 0;
+          }
+        }
+      if (b.count) {
+        {
+          StageTimer t7(c, 7);
+          HIP_TRY(c, gemm_crt_launch(b, c->crt, s));
+        }
+        HIP_TRY(c, crt_combine_launch(b, c->crt, s));
+      }
+    }
+    return ACSE_OK;
+  }
   StageTimer t7(c, 7);  // the products alone
   // round t: the t-th summed spin pair of every output block (distinct outputs per launch)
   for (int t = 0; t < 4; ++t) {
@@ -3366,7 +3502,9 @@ acse_status spin_xa_from_blocks(acse_ctx c, SpinWs &w, int r, const double *Xaa,
 
 // The NY share of the spin-block map: S_b -= C_b for the three output blocks,
 // C = B - B(k<->l), B the contraction of X with the NY 3-cumulant of Eq. (8)
-// (App. D), in FP64 over spin-orbital tensors (n = 2r).  The 36 signed
+// (App. D), over spin-orbital tensors (n = 2r): the block products in FP64,
+// or with ACSE_INT8CRT on the int8 matrix cores in exact accumulation, the
+// rest in FP64.  The 36 signed
 // permutations of the cumulant product collapse by the pair antisymmetry of
 // the 2-cumulant and of X's lower pair into
 //   B = 4 [sw(t_il) + t_pl - 2 sw(t_ir) - 2 t_pr],  sw(t) = t - t(i<->j),
@@ -3386,14 +3524,15 @@ acse_status ny_spin_share(acse_ctx c, SpinWs &sw, const acse_problem_spin *p, co
   if (st != ACSE_OK) return st;
   SoWs &w = *wp;
   double *X = w.a[0], *C2 = w.a[1], *CS = w.a[2], *W = w.a[3], *T = w.a[4], *B = w.a[5];
+  const bool crt = c->crt_moduli != 0;  // the block products on the int8 matrix cores too
   if ((st = so_upload_sigma(c, w, c->ny_sigma)) != ACSE_OK) return st;
   HIP_TRY(c, launch_fill(n2 * n2, 0.0, X, s));
   for (int b : kSix) HIP_TRY(c, launch_so_embed(r, b, sw.XA[b], 1.0, X, s));
   HIP_TRY(c, launch_so_cumulant(r, ga, gb, p->d2aa, p->d2bb, p->d2ab, w.sig, C2, CS, s));
   // x = i, y = l; then the p, l term through Y
-  if ((st = so_contract(c, w, n, W, "kpia", X, "kprq", 1, C2, "iarq", 1, 1.0)) != ACSE_OK) return st;
+  if ((st = so_contract(c, w, n, W, "kpia", X, "kprq", 1, C2, "iarq", 1, 1.0, 0, crt)) != ACSE_OK) return st;
   HIP_TRY(c, launch_so_trace_y(n, W, w.Y, s));
-  if ((st = so_contract(c, w, n, T, "ijkl", W, "kpia", 1, CS, "jpal", 1, 1.0)) != ACSE_OK) return st;
+  if ((st = so_contract(c, w, n, T, "ijkl", W, "kpia", 1, CS, "jpal", 1, 1.0, 0, crt)) != ACSE_OK) return st;
   {
     Terms4 Q{};
     Q.n = 2;
@@ -3403,8 +3542,8 @@ acse_status ny_spin_share(acse_ctx c, SpinWs &sw, const acse_problem_spin *p, co
   }
   HIP_TRY(c, launch_so_tpl(n, 4.0, w.Y, CS, B, s));
   // x = i, y = r (the y = q products equal these)
-  if ((st = so_contract(c, w, n, W, "kqja", X, "kprq", 1, CS, "jpar", 1, 1.0)) != ACSE_OK) return st;
-  if ((st = so_contract(c, w, n, T, "ijkl", W, "kqja", 3, C2, "ialq", 1, 1.0)) != ACSE_OK) return st;
+  if ((st = so_contract(c, w, n, W, "kqja", X, "kprq", 1, CS, "jpar", 1, 1.0, 0, crt)) != ACSE_OK) return st;
+  if ((st = so_contract(c, w, n, T, "ijkl", W, "kqja", 3, C2, "ialq", 1, 1.0, 0, crt)) != ACSE_OK) return st;
   {
     Terms4 Q{};
     Q.n = 2;
@@ -3413,8 +3552,8 @@ acse_status ny_spin_share(acse_ctx c, SpinWs &sw, const acse_problem_spin *p, co
     HIP_TRY(c, launch_combine4(n, Q, B, 1, nullptr, s));
   }
   // x = p, y = r: accumulated straight into B
-  if ((st = so_contract(c, w, n, W, "kral", X, "kprq", 1, C2, "palq", 1, 1.0)) != ACSE_OK) return st;
-  if ((st = so_contract(c, w, n, B, "ijkl", W, "kral", 3, CS, "ijar", 1, -8.0, 1)) != ACSE_OK) return st;
+  if ((st = so_contract(c, w, n, W, "kral", X, "kprq", 1, C2, "palq", 1, 1.0, 0, crt)) != ACSE_OK) return st;
+  if ((st = so_contract(c, w, n, B, "ijkl", W, "kral", 3, CS, "ijar", 1, -8.0, 1, crt)) != ACSE_OK) return st;
   // S_b -= B_b - B_b(k<->l) on the spin block b of B
   for (int b : {B0000, B1111, B0101}) {
     const int64_t o0 = ((b >> 3) & 1) * (int64_t)r * n3, o1 = ((b >> 2) & 1) * (int64_t)r * n2;

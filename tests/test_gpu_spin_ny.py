@@ -167,9 +167,44 @@ def test_spin_ny_explicit_occupations(ctx):
         assert abs(g["norm2"] - o["norm2"]) <= TOL * o["norm2"]
 
 
+@pytest.mark.parametrize("name", ["fock_doublet_r3", "det_sz1_r4", "r6_4_2", "r13_8_5"])
+def test_spin_ny_int8crt_residual_and_step(ctx, name):
+    """int8 exact-accumulation products in both the Valdemoro part and the NY
+    share's spin-orbital block products (each operand sub-block converted to
+    residues on its own): residual and one step at the FP64 bar."""
+    p = PROBLEMS[name]()
+    sig = ost.sigma_open_shell(p["r"], p["Na"], p["Nb"])
+    print(f"[spin ny int8crt] {name}", flush=True)
+    raa, rbb, rab, n2 = ost.residual_spin(*_oracle_args(p), sigma_so=sig)
+    Raa, Rbb, Rab, gn2 = ctx.residual_spin(*_args(p), sigma=True, precision="int8crt")
+    _check_blocks(dict(R_aa=Raa, R_bb=Rbb, R_ab=Rab), dict(R_aa=raa, R_bb=rbb, R_ab=rab), ("R_aa", "R_bb", "R_ab"))
+    assert abs(gn2 - n2) <= TOL * n2
+    o = ost.step_spin(*_oracle_args(p), 1e-3, sigma_so=sig)
+    g = ctx.step_spin(*_args(p), eps=1e-3, return_ru=True, sigma=True, precision="int8crt")
+    _check_blocks(g, o, ("R_aa", "R_bb", "R_ab"))
+    _check_blocks(g, o, ("U_aa", "U_bb", "U_ab"))
+    _check_blocks(g, o, ("d2aa", "d2bb", "d2ab"))
+    assert abs(g["energy"] - o["energy"]) <= TOL * max(1.0, abs(o["energy"]))
+
+
+@pytest.mark.parametrize("r,Na,Nb", [(2, 1, 1), (4, 3, 0)])
+def test_spin_ny_int8crt_edge_counts(ctx, r, Na, Nb):
+    """int8 products at the smallest size and with an empty beta shell (whole
+    operand sub-blocks of zeros, row exponents of zero rows)."""
+    p = gen.spin_problem(r, Na, Nb, 2 * r, seed=70 + r + Na)
+    sig = ost.sigma_open_shell(r, Na, Nb)
+    print(f"[spin ny int8crt edge] r={r} Na={Na} Nb={Nb}", flush=True)
+    o = ost.step_spin(*_oracle_args(p), 1e-3, sigma_so=sig)
+    g = ctx.step_spin(*_args(p), eps=1e-3, return_ru=True, sigma=True, precision="int8crt")
+    for keys in (("R_aa", "R_bb", "R_ab"), ("U_aa", "U_bb", "U_ab"), ("d2aa", "d2bb", "d2ab")):
+        scale = max(np.abs(o[k]).max() for k in keys)
+        for k in keys:
+            assert np.abs(cpu(g[k]) - o[k]).max() <= TOL * max(scale, 1e-300), k
+
+
 def test_spin_ny_int8crt_masked(ctx):
-    """int8 exact-accumulation products of the Valdemoro part, the NY share in
-    FP64, with the active mask."""
+    """int8 exact-accumulation products (the Valdemoro part and the NY share's
+    block products) with the active mask."""
     p = gen.spin_problem(9, 5, 4, 18, seed=2)
     act = np.zeros(9, bool)
     act[[1, 2, 5, 7]] = True
