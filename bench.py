@@ -173,7 +173,8 @@ def bench_vjp(acse, gen, torch, modes, steps, warmup, ny_steps=2):
     same problem (one context per size).  With ny_steps > 0 also the NY
     residual's adjoint ("ny_fp64": the FP64 Valdemoro adjoint plus the NY
     share's, FP64 over spin-orbital tensors), ny_steps timed calls after one
-    warm-up, against the NY forward residual."""
+    warm-up, against the NY forward residual; "ny_int8crt" the same with the
+    int8 exact-accumulation products in both adjoints."""
     dev = torch.device("cuda", 0)
     res = {}
     for wl in ("vjp30", "r50"):
@@ -184,9 +185,9 @@ def bench_vjp(acse, gen, torch, modes, steps, warmup, ny_steps=2):
         Rb = [torch.as_tensor(a, device=dev).contiguous() for a in gen.cotangent(np.random.default_rng(5), r)]
         outs = [torch.empty_like(t) for t in keep]
         R = [torch.empty((r, r, r, r), dtype=torch.float64, device=dev) for _ in range(2)]
-        for mode in list(modes) + (["ny_fp64"] if ny_steps > 0 else []):
-            ny = mode == "ny_fp64"
-            opts = acse.Context.options("fp64" if ny else mode, sigma=True if ny else None)
+        for mode in list(modes) + (["ny_fp64", "ny_int8crt"] if ny_steps > 0 else []):
+            ny = mode.startswith("ny_")
+            opts = acse.Context.options(mode[3:] if ny else mode, sigma=True if ny else None)
             if not ny:
                 ctx.autotune_raw(prob, opts)
             n_warm, n_steps = (1, ny_steps) if ny else (warmup, steps)

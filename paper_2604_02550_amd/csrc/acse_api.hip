@@ -1803,8 +1803,9 @@ Term4 so_term(const double *in, double cf, int64_t s0, int64_t s1, int64_t s2, i
 // X_A embedded as a spin-orbital tensor): the cotangent of B from
 // (Rbar_aa, Rbar_ab), then back through the pairwise contractions of B (the
 // forward intermediates recomputed), the trace Y, the sigma weighting and the
-// 2-cumulant to X, the 2-RDM and the 1-RDM, all FP64 over n = 2r spin
-// orbitals: 3 forward and 12 backward n^2 x n^2 x n^2 GEMMs.  The results are
+// 2-cumulant to X, the 2-RDM and the 1-RDM, over n = 2r spin orbitals: 3
+// forward and 12 backward n^2 x n^2 x n^2 GEMMs (FP64, or int8 exact-
+// accumulation products under ACSE_INT8CRT), the rest in FP64.  The results are
 // added to the Valdemoro adjoint's accumulators: Abaa, Abab (gradients of the
 // fold's blocks), Gbaa, Gbab (half the gradients of d2aa, d2ab) and gbar (the
 // 1-RDM's), before their projections.
@@ -1814,6 +1815,7 @@ acse_status ny_vjp_share_run(acse_ctx c, const acse_problem *p, const double *Aa
   const int r = p->r, n = 2 * r;
   const int64_t n2 = (int64_t)n * n, n3 = n2 * n;
   hipStream_t s = c->stream;
+  const bool crt = c->crt_moduli != 0;  // block products on the int8 matrix cores
   StageTimer t6(c, 6);
   SoWs *wp = nullptr;
   acse_status st = ensure_so_ws(c, n, 12, wp);
@@ -1827,10 +1829,10 @@ acse_status ny_vjp_share_run(acse_ctx c, const acse_problem *p, const double *Aa
   // forward: X, the cumulants, the three first-stage intermediates, Y
   HIP_TRY(c, launch_so_embed_singlet_x(r, Aaa, Aab, X, s));
   HIP_TRY(c, launch_so_cumulant(r, p->d1, p->d1, p->d2aa, p->d2aa, p->d2ab, w.sig, C2, CS, s));
-  if ((st = so_contract(c, w, n, W1, "kpia", X, "kprq", 1, C2, "iarq", 1, 1.0)) != ACSE_OK) return st;
+  if ((st = so_contract(c, w, n, W1, "kpia", X, "kprq", 1, C2, "iarq", 1, 1.0, 0, crt)) != ACSE_OK) return st;
   HIP_TRY(c, launch_so_trace_y(n, W1, w.Y, s));
-  if ((st = so_contract(c, w, n, M2, "kqja", X, "kprq", 1, CS, "jpar", 1, 1.0)) != ACSE_OK) return st;
-  if ((st = so_contract(c, w, n, M3, "kral", X, "kprq", 1, C2, "palq", 1, 1.0)) != ACSE_OK) return st;
+  if ((st = so_contract(c, w, n, M2, "kqja", X, "kprq", 1, CS, "jpar", 1, 1.0, 0, crt)) != ACSE_OK) return st;
+  if ((st = so_contract(c, w, n, M3, "kral", X, "kprq", 1, C2, "palq", 1, 1.0, 0, crt)) != ACSE_OK) return st;
   // cotangent of B; Tb = sw(Bbar), the cotangent shape of the sw() terms
   HIP_TRY(c, launch_so_bbar(r, Rbar_aa, Rbar_ab, 1.0, Bb, s));
   {
@@ -1841,23 +1843,23 @@ acse_status ny_vjp_share_run(acse_ctx c, const acse_problem *p, const double *Aa
     HIP_TRY(c, launch_combine4(n, Q, Tb, 0, nullptr, s));
   }
   // t_il (weight 4 on sw) and t_pl (weight 4, through Y)
-  if ((st = so_contract(c, w, n, Wb, "kpia", Tb, "ijkl", 1, CS, "jpal", 1, 4.0)) != ACSE_OK) return st;
+  if ((st = so_contract(c, w, n, Wb, "kpia", Tb, "ijkl", 1, CS, "jpal", 1, 4.0, 0, crt)) != ACSE_OK) return st;
   HIP_TRY(c, launch_so_ybar(n, 4.0, Bb, CS, w.Yb, s));
   HIP_TRY(c, launch_so_diag_add(n, w.Yb, Wb, s));
-  if ((st = so_contract(c, w, n, CSb, "jpal", Tb, "ijkl", 1, W1, "kpia", 1, 4.0)) != ACSE_OK) return st;
+  if ((st = so_contract(c, w, n, CSb, "jpal", Tb, "ijkl", 1, W1, "kpia", 1, 4.0, 0, crt)) != ACSE_OK) return st;
   HIP_TRY(c, launch_so_csbar_pl(n, 4.0, Bb, w.Y, CSb, s));
-  if ((st = so_contract(c, w, n, Xb, "kprq", Wb, "kpia", 1, C2, "iarq", 1, 1.0)) != ACSE_OK) return st;
-  if ((st = so_contract(c, w, n, C2b, "iarq", Wb, "kpia", 1, X, "kprq", 1, 1.0)) != ACSE_OK) return st;
+  if ((st = so_contract(c, w, n, Xb, "kprq", Wb, "kpia", 1, C2, "iarq", 1, 1.0, 0, crt)) != ACSE_OK) return st;
+  if ((st = so_contract(c, w, n, C2b, "iarq", Wb, "kpia", 1, X, "kprq", 1, 1.0, 0, crt)) != ACSE_OK) return st;
   // t_ir (weight -8 on sw)
-  if ((st = so_contract(c, w, n, Wb, "kqja", Tb, "ijkl", 1, C2, "ialq", 1, -8.0)) != ACSE_OK) return st;
-  if ((st = so_contract(c, w, n, C2b, "ialq", Tb, "ijkl", 1, M2, "kqja", 3, -8.0, 1)) != ACSE_OK) return st;
-  if ((st = so_contract(c, w, n, Xb, "kprq", Wb, "kqja", 3, CS, "jpar", 1, 1.0, 1)) != ACSE_OK) return st;
-  if ((st = so_contract(c, w, n, CSb, "jpar", Wb, "kqja", 3, X, "kprq", 1, 1.0, 1)) != ACSE_OK) return st;
+  if ((st = so_contract(c, w, n, Wb, "kqja", Tb, "ijkl", 1, C2, "ialq", 1, -8.0, 0, crt)) != ACSE_OK) return st;
+  if ((st = so_contract(c, w, n, C2b, "ialq", Tb, "ijkl", 1, M2, "kqja", 3, -8.0, 1, crt)) != ACSE_OK) return st;
+  if ((st = so_contract(c, w, n, Xb, "kprq", Wb, "kqja", 3, CS, "jpar", 1, 1.0, 1, crt)) != ACSE_OK) return st;
+  if ((st = so_contract(c, w, n, CSb, "jpar", Wb, "kqja", 3, X, "kprq", 1, 1.0, 1, crt)) != ACSE_OK) return st;
   // t_pr (weight -8)
-  if ((st = so_contract(c, w, n, Wb, "kral", Bb, "ijkl", 1, CS, "ijar", 1, -8.0)) != ACSE_OK) return st;
-  if ((st = so_contract(c, w, n, CSb, "ijar", Bb, "ijkl", 1, M3, "kral", 3, -8.0, 1)) != ACSE_OK) return st;
-  if ((st = so_contract(c, w, n, Xb, "kprq", Wb, "kral", 3, C2, "palq", 1, 1.0, 1)) != ACSE_OK) return st;
-  if ((st = so_contract(c, w, n, C2b, "palq", Wb, "kral", 3, X, "kprq", 1, 1.0, 1)) != ACSE_OK) return st;
+  if ((st = so_contract(c, w, n, Wb, "kral", Bb, "ijkl", 1, CS, "ijar", 1, -8.0, 0, crt)) != ACSE_OK) return st;
+  if ((st = so_contract(c, w, n, CSb, "ijar", Bb, "ijkl", 1, M3, "kral", 3, -8.0, 1, crt)) != ACSE_OK) return st;
+  if ((st = so_contract(c, w, n, Xb, "kprq", Wb, "kral", 3, C2, "palq", 1, 1.0, 1, crt)) != ACSE_OK) return st;
+  if ((st = so_contract(c, w, n, C2b, "palq", Wb, "kral", 3, X, "kprq", 1, 1.0, 1, crt)) != ACSE_OK) return st;
   // cs = sigma_a c2, c2 = 2D - (1D^1D)/2, then the singlet lifts
   HIP_TRY(c, launch_so_sigma_fold(n, w.sig, CSb, C2b, s));
   HIP_TRY(c, launch_so_d1bar_singlet(r, p->d1, C2b, gbar, s));

@@ -291,10 +291,13 @@ def test_residual_vjp_ny_smallest_sizes(ctx, r, N):
         assert maxrel(got[k], ref[k]) < TOL64, (k, maxrel(got[k], ref[k]))
 
 
-def test_residual_vjp_ny_int8crt_vs_oracle(ctx):
-    p = PROBLEMS["r10"]()
+@pytest.mark.parametrize("name", ["r6", "r10", "r13"])
+def test_residual_vjp_ny_int8crt_vs_oracle(ctx, name):
+    """The NY adjoint with int8 exact-accumulation products in both the
+    Valdemoro part and the NY share's spin-orbital contractions, at the FP64 bar."""
+    p = PROBLEMS[name]()
     sig = ny_sigma(p, "scattered")
-    print("[residual_vjp_ny] r10 int8crt", flush=True)
+    print(f"[residual_vjp_ny] {name} int8crt", flush=True)
     Rb = gen.cotangent(np.random.default_rng(32), p["r"])
     ref = adj.residual_vjp(p["h"], p["V"], p["N"], p["gamma"], p["d2aa"], p["d2ab"], *Rb, sigma=sig)
     got = gpu_vjp(ctx, p, Rb, "int8crt", sigma=sig)
