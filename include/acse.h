@@ -158,14 +158,18 @@ typedef struct {
  *                  the NY shares run in order on the context's stream.  The
  *                  adjoint (acse_residual_vjp) and the quadratic step control
  *                  of acse_solve (which needs it) take the NY share's adjoint
- *                  for r <= 64 (ACSE_ERR_UNSUPPORTED above): FP64 over
+ *                  for r <= 64 (ACSE_ERR_UNSUPPORTED above): over
  *                  spin-orbital tensors (n = 2r) as 15 pairwise contractions,
  *                  each run as the 10 of its 64 r^2 x r^2 x r^2 spin-block
- *                  products whose operand blocks conserve spin; its first call
- *                  allocating 12 n^4 doubles and two operand buffers of
- *                  16 round_up(r^2, 256) round_up(r^2, 64) doubles for its r
- *                  (1.9 GB at r = 32, 11.3 GB at r = 50), reallocated when a
- *                  larger r comes, kept until acse_destroy. */
+ *                  products whose operand blocks conserve spin (FP64, or int8
+ *                  exact-accumulation products under ACSE_INT8CRT; the rest
+ *                  FP64); its first call allocating 12 n^4 doubles and two
+ *                  operand buffers of 16 round_up(r^2, 256) round_up(r^2, 64)
+ *                  doubles for its r (1.9 GB at r = 32, 11.3 GB at r = 50),
+ *                  its first ACSE_INT8CRT call the residues of the 32 operand
+ *                  sub-blocks and of one launch's six products (3.7 GB at
+ *                  r = 50), reallocated when a larger r comes, kept until
+ *                  acse_destroy. */
 typedef enum { ACSE_RECON_V = 0, ACSE_RECON_NY = 1 } acse_reconstruction;
 
 /* acse_options.flags: run the general-size kernels at every r (the one-index
