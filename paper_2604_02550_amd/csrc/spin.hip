@@ -202,34 +202,49 @@ __global__ void __launch_bounds__(256) k_so_trace_y(int n, const double *__restr
   Y[e] = acc;
 }
 
-// One thread per (i, j, four consecutive k of one spin, l): the sum over a in
-// a fixed order, each cs element read once for the four k.  Y and cs conserve
-// spin (Y_ka is zero unless a has the spin of k), so only the spin-conserving
-// outputs receive a contribution, and a runs over the spin orbitals of k's spin.
+// t_pl: B[i,j,k,l] += c sum_a Y[k,a] cs[i,j,a,l].  Y and cs conserve spin
+// (Y_ka is zero unless a has the spin of k), so for given (i, j, l) only k and
+// a of the one spin sk = s_i + s_j - s_l contribute (none unless sk is 0 or
+// 1).  One thread per (i, j, l) keeps the r results of its k block in
+// registers; the two same-spin blocks of Y, transposed ([a][k]), sit in LDS
+// (2 r^2 doubles, 64 KB at r = 64); each conserving cs element is read once
+// and each output read and written once; the sum over a runs in a fixed
+// order.
+constexpr int kTplMaxR = 64;
 __global__ void __launch_bounds__(256)
 k_so_tpl(int n, double c, const double *__restrict__ Y, const double *__restrict__ cs, double *__restrict__ B) {
-  const int r = n / 2, kq = (r + 3) / 4;  // k groups per spin
+  extern __shared__ double tpl_yt[];  // [spin][a][k] = Y[spin r + k][spin r + a]
+  const int r = n / 2;
+  const int rr = r * r;
+  for (int e = threadIdx.x; e < 2 * rr; e += 256) {
+    const int sp = e / rr, q = e - sp * rr, a = q / r, k = q - a * r;
+    tpl_yt[e] = Y[(int64_t)(sp * r + k) * n + sp * r + a];
+  }
+  __syncthreads();
   const int64_t n2 = (int64_t)n * n;
   const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  if (e >= n2 * 2 * kq * n) return;
+  if (e >= n2 * n) return;
   const int l = (int)(e % n);
-  const int64_t rest = e / n;
-  const int g = (int)(rest % (2 * kq));
-  const int64_t ij = rest / (2 * kq);
+  const int64_t ij = e / n;
   const int i = (int)(ij / n), j = (int)(ij % n);
-  const int sk = g / kq, k0 = sk * r + (g % kq) * 4;
-  const int kend = min(k0 + 4, sk * r + r);
-  if ((i >= r) + (j >= r) != sk + (l >= r)) return;
-  const double *q = cs + ij * n2 + l;
-  double acc[4] = {0.0, 0.0, 0.0, 0.0};
-  for (int a = sk * r; a < sk * r + r; ++a) {
-    const double v = q[(int64_t)a * n];
+  const int sk = (i >= r) + (j >= r) - (l >= r);
+  if (sk < 0 || sk > 1) return;
+  const double *q = cs + ij * n2 + (int64_t)sk * r * n + l;
+  const double *yb = tpl_yt + sk * rr;
+  double acc[kTplMaxR];
 #pragma unroll
-    for (int t = 0; t < 4; ++t)
-      if (k0 + t < kend) acc[t] += Y[(int64_t)(k0 + t) * n + a] * v;
+  for (int t = 0; t < kTplMaxR; ++t) acc[t] = 0.0;
+  for (int a = 0; a < r; ++a) {
+    const double v = q[(int64_t)a * n];
+    const double *ya = yb + a * r;
+#pragma unroll
+    for (int t = 0; t < kTplMaxR; ++t)
+      if (t < r) acc[t] += ya[t] * v;
   }
-  for (int t = 0; t < 4; ++t)
-    if (k0 + t < kend) B[ij * n2 + (int64_t)(k0 + t) * n + l] += c * acc[t];
+  double *bo = B + ij * n2 + (int64_t)sk * r * n + l;
+#pragma unroll
+  for (int t = 0; t < kTplMaxR; ++t)
+    if (t < r) bo[(int64_t)t * n] += c * acc[t];
 }
 
 // One workgroup per (letter values of the two positions other than u and 3),
@@ -541,8 +556,10 @@ hipError_t launch_so_trace_y(int n, const double *W, double *Y, hipStream_t s) {
 }
 
 hipError_t launch_so_tpl(int n, double c, const double *Y, const double *cs, double *B, hipStream_t s) {
-  const int r = n / 2, kq = (r + 3) / 4;
-  hipLaunchKernelGGL(k_so_tpl, grid1((int64_t)n * n * 2 * kq * n), dim3(256), 0, s, n, c, Y, cs, B);
+  const int r = n / 2;
+  if (r > kTplMaxR) return hipErrorInvalidValue;
+  const size_t lds = 2 * (size_t)r * r * sizeof(double);
+  hipLaunchKernelGGL(k_so_tpl, grid1((int64_t)n * n * n), dim3(256), lds, s, n, c, Y, cs, B);
   return hipGetLastError();
 }
 
