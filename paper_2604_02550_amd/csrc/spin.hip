@@ -419,22 +419,46 @@ k_so_ybar(int n, double c, const double *__restrict__ Bb, const double *__restri
   }
 }
 
+// csbar[i,j,a,l] += c sum_k Bbar[i,j,k,l] Y[k,a] over the conserving
+// elements: for given (i, j, l) the spin sa = s_i + s_j - s_l of a (none
+// unless 0 or 1) is also k's (Y conserves spin).  One thread per (i, j, l)
+// keeps the r results of its a block in registers, Y's two same-spin blocks
+// ([k][a]) sit in LDS, and each conserving Bbar element is read once; the sum
+// over k runs in a fixed order.
 __global__ void __launch_bounds__(256)
 k_so_csbar_pl(int n, double c, const double *__restrict__ Bb, const double *__restrict__ Y, double *__restrict__ CSb) {
+  extern __shared__ double csb_y[];  // [spin][k][a] = Y[spin r + k][spin r + a]
+  const int r = n / 2;
+  const int rr = r * r;
+  for (int e = threadIdx.x; e < 2 * rr; e += 256) {
+    const int sp = e / rr, q = e - sp * rr, k = q / r, a = q - k * r;
+    csb_y[e] = Y[(int64_t)(sp * r + k) * n + sp * r + a];
+  }
+  __syncthreads();
   const int64_t n2 = (int64_t)n * n;
   const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  if (e >= n2 * n2) return;
-  const int r = n / 2;
-  const int l = (int)(e % n), a = (int)((e / n) % n), j = (int)((e / n2) % n), i = (int)(e / (n2 * n));
-  // Bbar and Y conserve spin: only conserving (i,j,a,l) receive a
-  // contribution, and k runs over the spin orbitals of a's spin
-  if ((i >= r) + (j >= r) != (a >= r) + (l >= r)) return;
-  const int64_t ij = e / n2;
-  const int k0 = a >= r ? r : 0;
-  const double *b = Bb + ij * n2 + l;
-  double acc = 0.0;
-  for (int k = k0; k < k0 + r; ++k) acc += b[(int64_t)k * n] * Y[(int64_t)k * n + a];
-  CSb[e] += c * acc;
+  if (e >= n2 * n) return;
+  const int l = (int)(e % n);
+  const int64_t ij = e / n;
+  const int i = (int)(ij / n), j = (int)(ij % n);
+  const int sa = (i >= r) + (j >= r) - (l >= r);
+  if (sa < 0 || sa > 1) return;
+  const double *b = Bb + ij * n2 + (int64_t)sa * r * n + l;
+  const double *yb = csb_y + sa * rr;
+  double acc[kTplMaxR];
+#pragma unroll
+  for (int t = 0; t < kTplMaxR; ++t) acc[t] = 0.0;
+  for (int k = 0; k < r; ++k) {
+    const double v = b[(int64_t)k * n];
+    const double *yk = yb + k * r;
+#pragma unroll
+    for (int t = 0; t < kTplMaxR; ++t)
+      if (t < r) acc[t] += v * yk[t];
+  }
+  double *o = CSb + ij * n2 + (int64_t)sa * r * n + l;
+#pragma unroll
+  for (int t = 0; t < kTplMaxR; ++t)
+    if (t < r) o[(int64_t)t * n] += c * acc[t];
 }
 
 __global__ void __launch_bounds__(256) k_so_diag_add(int n, const double *__restrict__ Yb, double *__restrict__ Wb) {
@@ -617,7 +641,10 @@ hipError_t launch_so_ybar(int n, double c, const double *Bbar, const double *cs,
 }
 
 hipError_t launch_so_csbar_pl(int n, double c, const double *Bbar, const double *Y, double *CSbar, hipStream_t s) {
-  hipLaunchKernelGGL(k_so_csbar_pl, grid1((int64_t)n * n * n * n), dim3(256), 0, s, n, c, Bbar, Y, CSbar);
+  const int r = n / 2;
+  if (r > kTplMaxR) return hipErrorInvalidValue;
+  const size_t lds = 2 * (size_t)r * r * sizeof(double);
+  hipLaunchKernelGGL(k_so_csbar_pl, grid1((int64_t)n * n * n), dim3(256), lds, s, n, c, Bbar, Y, CSbar);
   return hipGetLastError();
 }
 
