@@ -1475,6 +1475,7 @@ struct SoWs {
   int n = 0, narr = 0;
   double *a[kSoMaxArrays] = {};
   double *opA = nullptr, *opB = nullptr, *Y = nullptr, *Yb = nullptr, *sig = nullptr;
+  double *part = nullptr;        // kSoYbarParts * n^2 / 2 partial sums of Ybar
   std::vector<double> sig_host;  // what sig holds
   int op_r = 0;                  // r whose operand layout the padding of opA / opB was cleared for
   // int8 products (ACSE_INT8CRT): residue planes and row exponents of each of
@@ -1513,7 +1514,8 @@ acse_status ensure_so_ws(acse_ctx c, int n, int narr, SoWs *&out) {
   const int64_t n2 = (int64_t)nn * nn;
   const int64_t nat = round_up(n2 * n2 * 8, 256), opb = round_up(so_op_doubles(nn / 2) * 8, 256);
   const int64_t sm = round_up(n2 * 8, 256);
-  const int64_t bytes = na * nat + 2 * opb + 2 * sm + round_up((int64_t)nn * 8, 256);
+  const int64_t pb = round_up((int64_t)kSoYbarParts * (n2 / 2) * 8, 256);
+  const int64_t bytes = na * nat + 2 * opb + 2 * sm + round_up((int64_t)nn * 8, 256) + pb;
   if (hipMalloc(&w->base, bytes) != hipSuccess) {
     (void)hipGetLastError();
     w->base = nullptr;
@@ -1528,6 +1530,7 @@ acse_status ensure_so_ws(acse_ctx c, int n, int narr, SoWs *&out) {
   w->Y = take(sm);
   w->Yb = take(sm);
   w->sig = take(round_up((int64_t)nn * 8, 256));
+  w->part = take(pb);
   w->n = nn;
   w->narr = na;
   w->sig_host.clear();
@@ -1844,7 +1847,7 @@ acse_status ny_vjp_share_run(acse_ctx c, const acse_problem *p, const double *Aa
   }
   // t_il (weight 4 on sw) and t_pl (weight 4, through Y)
   if ((st = so_contract(c, w, n, Wb, "kpia", Tb, "ijkl", 1, CS, "jpal", 1, 4.0, 0, crt)) != ACSE_OK) return st;
-  HIP_TRY(c, launch_so_ybar(n, 4.0, Bb, CS, w.Yb, s));
+  HIP_TRY(c, launch_so_ybar(n, 4.0, Bb, CS, w.part, w.Yb, s));
   HIP_TRY(c, launch_so_diag_add(n, w.Yb, Wb, s));
   if ((st = so_contract(c, w, n, CSb, "jpal", Tb, "ijkl", 1, W1, "kpia", 1, 4.0, 0, crt)) != ACSE_OK) return st;
   HIP_TRY(c, launch_so_csbar_pl(n, 4.0, Bb, w.Y, CSb, s));

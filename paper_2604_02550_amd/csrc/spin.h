@@ -104,7 +104,10 @@ hipError_t launch_so_dbar_singlet(int r, double c, const double *D, double *Gaa,
 hipError_t launch_so_bbar(int r, const double *Rbar_aa, const double *Rbar_ab, double sign, double *Bbar,
                           hipStream_t s);
 // Ybar[k,a] = c sum_{i,j,l} Bbar[i,j,k,l] cs[i,j,a,l] (fixed summation order).
-hipError_t launch_so_ybar(int n, double c, const double *Bbar, const double *cs, double *Ybar, hipStream_t s);
+// part: kSoYbarParts * n^2 / 2 doubles of scratch (the per-workgroup partial sums).
+constexpr int kSoYbarParts = 512;
+hipError_t launch_so_ybar(int n, double c, const double *Bbar, const double *cs, double *part, double *Ybar,
+                          hipStream_t s);
 // CSbar[i,j,a,l] += c sum_k Bbar[i,j,k,l] Y[k,a].
 hipError_t launch_so_csbar_pl(int n, double c, const double *Bbar, const double *Y, double *CSbar, hipStream_t s);
 // Wbar[k,p,p,a] += Ybar[k,a] for every p (adjoint of the trace Y = sum_p W[k,p,p,a]).

@@ -370,53 +370,94 @@ k_so_bbar(int r, const double *__restrict__ Raa, const double *__restrict__ Rab,
   Bb[e] = -rb(I, J, K, L) + rb(I, J, L, K) + sign * (rb(K, L, I, J) - rb(L, K, I, J));
 }
 
-// One workgroup of 256 per (k, a-tile of 8 spin orbitals of k's spin): the
-// threads stride over the (i, j, l) that conserve spin with k (l fastest),
-// each B element read once for the eight a; fixed-order reductions.  Bbar
-// and cs conserve spin, so Ybar vanishes unless a has the spin of k.
+// Ybar[k,a] = c sum_{i,j,l} Bbar[i,j,k,l] cs[i,j,a,l] over the conserving
+// elements: a and k share one spin sa, and for given (i, j) the spin of l is
+// s_i + s_j - sa.  Split over (i, j): workgroup w takes a contiguous range of
+// (i, j) and, per spin case, stages the r x r blocks Bbar[i,j,sa.,sl.] and
+// cs[i,j,sa.,sl.] in LDS (rows padded to r + 1), each thread accumulating up
+// to two 4 x 4 register blocks of its partial Ybar (both spin blocks, 2 r^2
+// values per workgroup); a second pass sums the partials over the workgroups
+// in a fixed order.  Every conserving Bbar and cs element is read once.
+constexpr int kYbB = 4;
 __global__ void __launch_bounds__(256)
-k_so_ybar(int n, double c, const double *__restrict__ Bb, const double *__restrict__ cs, double *__restrict__ Yb) {
-  constexpr int TA = 8;
-  __shared__ double part[4][TA];
-  const int r = n / 2, at = (r + TA - 1) / TA;
-  const int k = blockIdx.x / (2 * at), rest = blockIdx.x % (2 * at);
-  const int sa = rest / at, a0 = (rest % at) * TA;  // a = sa r + a0 + t
-  const int sk = k >= r;
+k_so_ybar_part(int n, const double *__restrict__ Bb, const double *__restrict__ cs, double *__restrict__ part) {
+  extern __shared__ double ybar_s[];
+  const int r = n / 2, rp = r + 1, nb = (r + kYbB - 1) / kYbB, nblk = 2 * nb * nb;
+  double *const TB = ybar_s, *const CB = ybar_s + r * rp;
   const int64_t n2 = (int64_t)n * n;
-  if (sa != sk) {  // zero
-    if (threadIdx.x < TA && a0 + (int)threadIdx.x < r) Yb[(int64_t)k * n + sa * r + a0 + threadIdx.x] = 0.0;
-    return;
-  }
-  double acc[TA];
-  for (int t = 0; t < TA; ++t) acc[t] = 0.0;
-  // (s_i, s_j, s_l) with s_i + s_j = s_k + s_l: for each of the two s_l, the
-  // (s_i, s_j) pairs with that sum; flattened over (i, j, l) of the spin case
-  for (int sl = 0; sl < 2; ++sl) {
-    const int tot_s = sk + sl;
-    for (int si = 0; si < 2; ++si) {
-      const int sj = tot_s - si;
-      if (sj < 0 || sj > 1) continue;
-      const int64_t cnt = (int64_t)r * r * r;
-      for (int64_t e = threadIdx.x; e < cnt; e += 256) {
-        const int l = (int)(e % r), j = (int)((e / r) % r), i = (int)(e / ((int64_t)r * r));
-        const int64_t ij = (int64_t)(i + si * r) * n + (j + sj * r);
-        const double bv = Bb[ij * n2 + (int64_t)k * n + l + sl * r];
-        const double *q = cs + ij * n2 + (int64_t)(sa * r + a0) * n + l + sl * r;
-        for (int t = 0; t < TA; ++t)
-          if (a0 + t < r) acc[t] += bv * q[(int64_t)t * n];
+  const int64_t ij0 = n2 * blockIdx.x / gridDim.x, ij1 = n2 * (blockIdx.x + 1) / gridDim.x;
+  double acc[2][kYbB][kYbB];
+#pragma unroll
+  for (int q = 0; q < 2; ++q)
+#pragma unroll
+    for (int u = 0; u < kYbB; ++u)
+#pragma unroll
+      for (int v = 0; v < kYbB; ++v) acc[q][u][v] = 0.0;
+  for (int64_t ij = ij0; ij < ij1; ++ij) {
+    const int i = (int)(ij / n), j = (int)(ij % n);
+    const int st = (i >= r) + (j >= r);
+    for (int sa = 0; sa < 2; ++sa) {
+      const int sl = st - sa;
+      if (sl < 0 || sl > 1) continue;  // the same for the whole workgroup
+      __syncthreads();                 // the previous blocks are fully read
+      const double *tb = Bb + ij * n2 + (int64_t)sa * r * n + sl * r;
+      const double *cb = cs + ij * n2 + (int64_t)sa * r * n + sl * r;
+      for (int e = threadIdx.x; e < r * r; e += 256) {
+        const int x = e / r, l = e - x * r;
+        TB[x * rp + l] = tb[(int64_t)x * n + l];
+        CB[x * rp + l] = cb[(int64_t)x * n + l];
+      }
+      __syncthreads();
+#pragma unroll
+      for (int q = 0; q < 2; ++q) {
+        const int bb = threadIdx.x + 256 * q;
+        if (bb >= nblk || bb / (nb * nb) != sa) continue;
+        const int k0 = ((bb % (nb * nb)) / nb) * kYbB, a0 = (bb % nb) * kYbB;
+        for (int l = 0; l < r; ++l) {
+          double tv[kYbB], cv[kYbB];
+#pragma unroll
+          for (int u = 0; u < kYbB; ++u) {
+            tv[u] = k0 + u < r ? TB[(k0 + u) * rp + l] : 0.0;
+            cv[u] = a0 + u < r ? CB[(a0 + u) * rp + l] : 0.0;
+          }
+#pragma unroll
+          for (int u = 0; u < kYbB; ++u)
+#pragma unroll
+            for (int v = 0; v < kYbB; ++v) acc[q][u][v] += tv[u] * cv[v];
+        }
       }
     }
   }
-  for (int t = 0; t < TA; ++t) {
-    double v = acc[t];
-    for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
-    if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6][t] = v;
+  double *po = part + (int64_t)blockIdx.x * 2 * r * r;  // [spin][k][a]
+#pragma unroll
+  for (int q = 0; q < 2; ++q) {
+    const int bb = threadIdx.x + 256 * q;
+    if (bb >= nblk) continue;
+    const int sa = bb / (nb * nb), k0 = ((bb % (nb * nb)) / nb) * kYbB, a0 = (bb % nb) * kYbB;
+#pragma unroll
+    for (int u = 0; u < kYbB; ++u)
+#pragma unroll
+      for (int v = 0; v < kYbB; ++v)
+        if (k0 + u < r && a0 + v < r) po[((int64_t)sa * r + k0 + u) * r + a0 + v] = acc[q][u][v];
   }
-  __syncthreads();
-  if (threadIdx.x < TA && a0 + (int)threadIdx.x < r) {
-    const int t = threadIdx.x;
-    Yb[(int64_t)k * n + sa * r + a0 + t] = c * (((part[0][t] + part[1][t]) + part[2][t]) + part[3][t]);
+}
+
+// Ybar = c x the sum of the partials in workgroup order; zero between spins.
+__global__ void __launch_bounds__(256)
+k_so_ybar_sum(int n, double c, const double *__restrict__ part, int nparts, double *__restrict__ Yb) {
+  const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (e >= (int64_t)n * n) return;
+  const int r = n / 2;
+  const int k = (int)(e / n), a = (int)(e % n);
+  const int sk = k >= r;
+  if ((a >= r) != sk) {
+    Yb[e] = 0.0;
+    return;
   }
+  const int64_t o = ((int64_t)sk * r + (k - sk * r)) * r + (a - sk * r), stride = 2 * (int64_t)r * r;
+  double acc = 0.0;
+  for (int w = 0; w < nparts; ++w) acc += part[w * stride + o];
+  Yb[e] = c * acc;
 }
 
 // csbar[i,j,a,l] += c sum_k Bbar[i,j,k,l] Y[k,a] over the conserving
@@ -634,9 +675,21 @@ hipError_t launch_so_bbar(int r, const double *Rbar_aa, const double *Rbar_ab, d
   return hipGetLastError();
 }
 
-hipError_t launch_so_ybar(int n, double c, const double *Bbar, const double *cs, double *Ybar, hipStream_t s) {
+hipError_t launch_so_ybar(int n, double c, const double *Bbar, const double *cs, double *part, double *Ybar,
+                          hipStream_t s) {
   const int r = n / 2;
-  hipLaunchKernelGGL(k_so_ybar, dim3((unsigned)(n * 2 * ((r + 7) / 8))), dim3(256), 0, s, n, c, Bbar, cs, Ybar);
+  if (r > kTplMaxR) return hipErrorInvalidValue;
+  const size_t lds = 2 * (size_t)r * (r + 1) * sizeof(double);
+  static bool attr = false;
+  if (!attr) {
+    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(&k_so_ybar_part),
+                                       hipFuncAttributeMaxDynamicSharedMemorySize,
+                                       (int)(2 * (size_t)kTplMaxR * (kTplMaxR + 1) * sizeof(double)));
+    if (e != hipSuccess) return e;
+    attr = true;
+  }
+  hipLaunchKernelGGL(k_so_ybar_part, dim3(kSoYbarParts), dim3(256), lds, s, n, Bbar, cs, part);
+  hipLaunchKernelGGL(k_so_ybar_sum, grid1((int64_t)n * n), dim3(256), 0, s, n, c, part, kSoYbarParts, Ybar);
   return hipGetLastError();
 }
 
